@@ -1,0 +1,266 @@
+"""ctypes wrapper of the FP64 CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this package.  The oracle (``oracle.c``) is a plain, slow FP64 implementation of
+one barotropic PISO step with Equilibrium-Eulerian dust, written from the
+method's equations; it shares no code with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SOURCES = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "conv.c")]
+
+MAX_CLASSES = 8
+MAX_CORR = 8
+
+OK, WARN_NOT_CONVERGED, ERR_INVALID, ERR_DIVERGED = 0, 1, -1, -3
+FLAG_PCG_MAXIT, FLAG_NONFINITE, FLAG_RHO_NONPOS, FLAG_KFACE_NONPOS = 1, 2, 4, 8
+
+RHO, U, PHI, RHO_P, P = 0, 1, 2, 3, 4
+SYS_B, SYS_W, SYS_PSIDT, SYS_K, SYS_X, SYS_P0, SYS_DIAG, SYS_USTAR = 10, 11, 12, 13, 14, 15, 16, 17
+
+STAT_KE, STAT_ENSTROPHY, STAT_RHO_RMS, STAT_MACH_RMS, STAT_MASS_GAS = 0, 1, 2, 3, 4
+STAT_CONC_VAR = 5
+STAT_MASS_P = 5 + MAX_CLASSES
+N_STATS = 5 + 2 * MAX_CLASSES
+
+
+class OraParams(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("n_classes", C.c_int32),
+        ("gamma", C.c_double), ("C", C.c_double), ("mu", C.c_double),
+        ("tau_p", C.c_double * MAX_CLASSES),
+        ("cfl", C.c_double), ("dt_growth", C.c_double), ("dt_fixed", C.c_double),
+        ("dt_max", C.c_double),
+        ("n_corr", C.c_int32), ("n_mom_sweeps", C.c_int32), ("n_dust_sweeps", C.c_int32),
+        ("p_tol", C.c_double), ("p_maxit", C.c_int32),
+    ]
+
+
+class OraInfo(C.Structure):
+    _fields_ = [
+        ("t", C.c_double), ("dt", C.c_double), ("courant", C.c_double),
+        ("pcg_iters", C.c_int32 * MAX_CORR), ("pcg_relres", C.c_double * MAX_CORR),
+        ("flags", C.c_int32), ("mass_gas", C.c_double),
+        ("mass_p", C.c_double * MAX_CLASSES),
+    ]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP) into ``liboracle.so``."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    srcs = [s for s in SOURCES if os.path.exists(s)]
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.ora_create.argtypes = [C.POINTER(OraParams), dp, dp, dp, C.POINTER(C.c_void_p)]
+        L.ora_create.restype = C.c_int
+        L.ora_step.argtypes = [C.c_void_p, C.c_int32, C.POINTER(OraInfo)]
+        L.ora_step.restype = C.c_int
+        L.ora_get.argtypes = [C.c_void_p, C.c_int32, C.c_int32, dp]
+        L.ora_get.restype = C.c_int
+        L.ora_stats.argtypes = [C.c_void_p, dp]
+        L.ora_stats.restype = C.c_int
+        L.ora_time.argtypes = [C.c_void_p]
+        L.ora_time.restype = C.c_double
+        L.ora_destroy.argtypes = [C.c_void_p]
+        L.ora_destroy.restype = None
+        L.ora_set_capture.argtypes = [C.c_void_p, C.c_int32]
+        L.ora_set_capture.restype = None
+        L.ora_num_threads.argtypes = []
+        L.ora_num_threads.restype = C.c_int
+        L.ora_i4.argtypes = [C.c_int32, C.c_int32, dp, dp]
+        L.ora_sngrad.argtypes = [C.c_int32, C.c_int32, dp, dp]
+        L.ora_div_flux.argtypes = [C.c_int32, dp, dp, dp, dp]
+        L.ora_grad.argtypes = [C.c_int32, dp, dp, dp, dp]
+        L.ora_div_vel.argtypes = [C.c_int32, dp, dp, dp, dp]
+        L.ora_lap.argtypes = [C.c_int32, dp, dp]
+        L.ora_kfaces.argtypes = [C.c_int32, dp, dp, dp, dp]
+        L.ora_helm_apply.argtypes = [C.c_int32, dp, dp, dp, dp, dp, dp]
+        L.ora_pcg.argtypes = [C.c_int32, dp, dp, dp, dp, dp, dp, C.c_double, C.c_int32, dp]
+        L.ora_pcg.restype = C.c_int32
+        if hasattr(L, "ora_conv_forward"):
+            _bind_conv(L)
+        _lib = L
+    return _lib
+
+
+def _bind_conv(L):
+    dp = C.POINTER(C.c_double)
+    L.ora_conv_forward.argtypes = [C.c_int32, C.c_int32, dp, dp, dp]
+    L.ora_conv_forward.restype = C.c_int
+    L.ora_conv_backward.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, dp, dp]
+    L.ora_conv_backward.restype = C.c_int
+    L.ora_conv_nweights.argtypes = []
+    L.ora_conv_nweights.restype = C.c_int32
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return int(lib().ora_num_threads())
+
+
+# ---------------------------------------------------------------- operators
+def i4(q, d):
+    q = _f64(q); out = np.empty_like(q)
+    lib().ora_i4(q.shape[0], d, _p(q), _p(out)); return out
+
+
+def sngrad(q, d):
+    q = _f64(q); out = np.empty_like(q)
+    lib().ora_sngrad(q.shape[0], d, _p(q), _p(out)); return out
+
+
+def div_flux(f):
+    f = [_f64(x) for x in f]; out = np.empty_like(f[0])
+    lib().ora_div_flux(f[0].shape[0], _p(f[0]), _p(f[1]), _p(f[2]), _p(out)); return out
+
+
+def grad(q):
+    q = _f64(q); g = [np.empty_like(q) for _ in range(3)]
+    lib().ora_grad(q.shape[0], _p(q), _p(g[0]), _p(g[1]), _p(g[2])); return g
+
+
+def div_vel(u):
+    u = [_f64(x) for x in u]; out = np.empty_like(u[0])
+    lib().ora_div_vel(u[0].shape[0], _p(u[0]), _p(u[1]), _p(u[2]), _p(out)); return out
+
+
+def lap(q):
+    q = _f64(q); out = np.empty_like(q)
+    lib().ora_lap(q.shape[0], _p(q), _p(out)); return out
+
+
+def kfaces(w):
+    w = _f64(w); k = [np.empty_like(w) for _ in range(3)]
+    lib().ora_kfaces(w.shape[0], _p(w), _p(k[0]), _p(k[1]), _p(k[2])); return k
+
+
+def helm_apply(psidt, K, x):
+    psidt = _f64(psidt); K = [_f64(k) for k in K]; x = _f64(x); y = np.empty_like(x)
+    lib().ora_helm_apply(x.shape[0], _p(psidt), _p(K[0]), _p(K[1]), _p(K[2]), _p(x), _p(y))
+    return y
+
+
+def pcg(psidt, K, b, x0=None, tol=1e-10, maxit=1000):
+    """Jacobi-PCG; returns (x, iterations, relres); iterations < 0 means not converged."""
+    psidt = _f64(psidt); K = [_f64(k) for k in K]; b = _f64(b)
+    x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
+    rel = C.c_double(0.0)
+    it = lib().ora_pcg(b.shape[0], _p(psidt), _p(K[0]), _p(K[1]), _p(K[2]), _p(b), _p(x),
+                       tol, maxit, C.byref(rel))
+    return x, int(it), rel.value
+
+
+# ---------------------------------------------------------------- whole step
+class Oracle:
+    """One oracle simulation state (host memory, FP64)."""
+
+    def __init__(self, n, rho, u, rho_p=None, *, gamma=1.4, C_=None, mu=1e-3, tau_p=(),
+                 cfl=0.5, dt_growth=1.2, dt_fixed=0.0, dt_max=0.0, n_corr=2, n_mom_sweeps=4,
+                 n_dust_sweeps=4, p_tol=1e-8, p_maxit=500, capture=False):
+        if C_ is None:
+            raise ValueError("closure constant C_ is required")
+        tau_p = tuple(tau_p)
+        prm = OraParams()
+        prm.n = n
+        prm.n_classes = len(tau_p)
+        prm.gamma, prm.C, prm.mu = gamma, C_, mu
+        for i, t in enumerate(tau_p):
+            prm.tau_p[i] = t
+        prm.cfl, prm.dt_growth, prm.dt_fixed, prm.dt_max = cfl, dt_growth, dt_fixed, dt_max
+        prm.n_corr, prm.n_mom_sweeps, prm.n_dust_sweeps = n_corr, n_mom_sweeps, n_dust_sweeps
+        prm.p_tol, prm.p_maxit = p_tol, p_maxit
+        self.prm = prm
+        self.n = n
+        self.K = len(tau_p)
+        rho = _f64(rho).reshape(n, n, n)
+        u = _f64(u).reshape(3, n, n, n)
+        rp = _f64(rho_p).reshape(self.K, n, n, n) if self.K else np.zeros(1)
+        h = C.c_void_p()
+        st = lib().ora_create(C.byref(prm), _p(rho), _p(u), _p(rp), C.byref(h))
+        if st != OK:
+            raise ValueError(f"ora_create failed with status {st}")
+        self._h = h
+        if capture:
+            lib().ora_set_capture(h, 1)
+
+    @classmethod
+    def from_case(cls, case, **kw):
+        return cls(case.n, case.rho, case.u, case.rho_p, gamma=case.gamma, C_=case.C, mu=case.mu,
+                   tau_p=case.tau_p, **kw)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.ora_destroy(h)
+            self._h = None
+
+    def step(self, n_steps=1):
+        """Advance n_steps; returns (status, list of info dicts)."""
+        infos = (OraInfo * max(n_steps, 1))()
+        st = lib().ora_step(self._h, n_steps, infos)
+        out = []
+        for i in range(n_steps):
+            r = infos[i]
+            out.append(dict(t=r.t, dt=r.dt, courant=r.courant,
+                            pcg_iters=list(r.pcg_iters[: self.prm.n_corr]),
+                            pcg_relres=list(r.pcg_relres[: self.prm.n_corr]),
+                            flags=r.flags, mass_gas=r.mass_gas,
+                            mass_p=list(r.mass_p[: self.K])))
+        return st, out
+
+    def get(self, which, corr=0):
+        n = self.n
+        count = {RHO: 1, U: 3, PHI: 3, RHO_P: max(self.K, 1), P: 1, SYS_K: 3,
+                 SYS_USTAR: 3}.get(which, 1)
+        out = np.empty((count, n, n, n))
+        st = lib().ora_get(self._h, which, corr, _p(out))
+        if st != OK:
+            raise ValueError(f"ora_get({which}) failed with status {st}")
+        if which == RHO_P:
+            return out[: self.K]
+        return out[0] if count == 1 else out
+
+    def stats(self):
+        out = np.zeros(N_STATS)
+        lib().ora_stats(self._h, _p(out))
+        K = self.K
+        return dict(ke=out[STAT_KE], enstrophy=out[STAT_ENSTROPHY], rho_rms=out[STAT_RHO_RMS],
+                    mach_rms=out[STAT_MACH_RMS], mass_gas=out[STAT_MASS_GAS],
+                    conc_var=list(out[STAT_CONC_VAR:STAT_CONC_VAR + K]),
+                    mass_p=list(out[STAT_MASS_P:STAT_MASS_P + K]))
+
+    @property
+    def t(self):
+        return lib().ora_time(self._h)

@@ -1,0 +1,117 @@
+/* oracle.h -- FP64 CPU oracle of one barotropic PISO step with
+ * Equilibrium-Eulerian dust transport (test infrastructure only).
+ *
+ * This library exists to check the GPU library.  Only the tests, the smoke
+ * check and the CPU-baseline leg of the benchmark load it.  It shares no code,
+ * header, constant or helper with the GPU path.
+ *
+ * Grid: periodic cube [0, 2 pi)^3 with n cells per side, spacing h = 2 pi / n,
+ * cell volume V = h^3, face area A = h^2.  Cell arrays hold n^3 doubles at
+ * offset i + n*(j + n*k) (x fastest).  Face array d holds, at the offset of
+ * cell P, the value on the face between P and P + e_d (face "P + 1/2 e_d").
+ */
+#ifndef PISO_ORACLE_H
+#define PISO_ORACLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORA_MAX_CLASSES 8
+#define ORA_MAX_CORR 8
+
+/* status codes (same meaning as the GPU library's) */
+#define ORA_OK 0
+#define ORA_WARN_NOT_CONVERGED 1
+#define ORA_ERR_INVALID (-1)
+#define ORA_ERR_DIVERGED (-3)
+
+/* info flags */
+#define ORA_FLAG_PCG_MAXIT 1
+#define ORA_FLAG_NONFINITE 2
+#define ORA_FLAG_RHO_NONPOS 4
+#define ORA_FLAG_KFACE_NONPOS 8
+
+typedef struct {
+    int32_t n;
+    int32_t n_classes;
+    double gamma, C, mu;
+    double tau_p[ORA_MAX_CLASSES];
+    double cfl, dt_growth, dt_fixed, dt_max;
+    int32_t n_corr, n_mom_sweeps, n_dust_sweeps;
+    double p_tol;
+    int32_t p_maxit;
+} ora_params;
+
+typedef struct {
+    double t, dt, courant;
+    int32_t pcg_iters[ORA_MAX_CORR];
+    double pcg_relres[ORA_MAX_CORR];
+    int32_t flags;
+    double mass_gas;
+    double mass_p[ORA_MAX_CLASSES];
+} ora_info;
+
+/* statistics, in this order */
+#define ORA_STAT_KE 0
+#define ORA_STAT_ENSTROPHY 1
+#define ORA_STAT_RHO_RMS 2
+#define ORA_STAT_MACH_RMS 3
+#define ORA_STAT_MASS_GAS 4
+#define ORA_STAT_CONC_VAR 5              /* n_classes entries */
+#define ORA_STAT_MASS_P (5 + ORA_MAX_CLASSES)  /* n_classes entries */
+#define ORA_N_STATS (5 + 2 * ORA_MAX_CLASSES)
+
+/* field selectors for ora_get */
+enum {
+    ORA_RHO = 0,      /* n^3 */
+    ORA_U = 1,        /* 3 n^3 */
+    ORA_PHI = 2,      /* 3 n^3 faces */
+    ORA_RHO_P = 3,    /* n_classes n^3 */
+    ORA_P = 4,        /* n^3: C rho^gamma */
+    /* pressure system of corrector `corr` of the last step */
+    ORA_SYS_B = 10,   /* right-hand side b */
+    ORA_SYS_W = 11,   /* rho/a_P at cell centres (face coefficient source) */
+    ORA_SYS_PSIDT = 12, /* psi/dt */
+    ORA_SYS_K = 13,   /* 3 n^3 face coefficients */
+    ORA_SYS_X = 14,   /* solution p' */
+    ORA_SYS_P0 = 15,  /* p(rho) at the corrector's start */
+    ORA_SYS_DIAG = 16, /* diagonal of M */
+    ORA_SYS_USTAR = 17 /* 3 n^3: momentum-predictor output u* of the last step */
+};
+
+typedef struct ora_state ora_state;
+
+/* ---- whole step ---- */
+int ora_create(const ora_params* prm, const double* rho, const double* u,
+               const double* rho_p, ora_state** out);
+int ora_step(ora_state* s, int32_t n_steps, ora_info* info);
+int ora_get(const ora_state* s, int32_t which, int32_t corr, double* dst);
+int ora_stats(const ora_state* s, double* out);
+double ora_time(const ora_state* s);
+void ora_destroy(ora_state* s);
+/* keep copies of each corrector's pressure system (b, w, psi/dt, K, p', p0, diag) */
+void ora_set_capture(ora_state* s, int32_t on);
+int ora_num_threads(void);
+
+/* ---- operators (exposed for the pins) ---- */
+void ora_i4(int32_t n, int32_t d, const double* q, double* out);
+void ora_sngrad(int32_t n, int32_t d, const double* q, double* out);
+void ora_div_flux(int32_t n, const double* f0, const double* f1, const double* f2, double* out);
+void ora_grad(int32_t n, const double* q, double* g0, double* g1, double* g2);
+void ora_div_vel(int32_t n, const double* u0, const double* u1, const double* u2, double* out);
+void ora_lap(int32_t n, const double* q, double* out);
+void ora_kfaces(int32_t n, const double* w, double* k0, double* k1, double* k2);
+void ora_helm_apply(int32_t n, const double* psidt, const double* k0, const double* k1,
+                    const double* k2, const double* x, double* y);
+int32_t ora_pcg(int32_t n, const double* psidt, const double* k0, const double* k1,
+                const double* k2, const double* b, double* x, double tol, int32_t maxit,
+                double* relres);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,341 @@
+"""Pins of the oracle's whole PISO + dust step.
+
+Closed forms (uniform-flow Fourier modes, acoustic period, Taylor-Green viscous
+decay), exact invariants (mass, free stream, rest state, the dusty-gas limit,
+translation and reflection equivariance, determinism), the corrector's fixed
+point and the predictor's conservation form.  Each is chosen so that a dropped term, a wrong sign, index
+or weight in the oracle breaks it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1404_0959_amd.inputs import make_hit_case, taylor_green_case
+
+GAMMA = 1.4
+
+
+def grid(n):
+    h = 2 * math.pi / n
+    xc = (np.arange(n) + 0.5) * h
+    z, y, x = np.meshgrid(xc, xc, xc, indexing="ij")
+    return h, (x, y, z)
+
+
+def uniform_state(n, U=(0.0, 0.0, 0.0)):
+    rho = np.ones((n, n, n))
+    u = np.stack([np.full((n, n, n), c) for c in U])
+    return rho, u
+
+
+# --------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("n_dust_sweeps", [2, 4])
+def test_dust_transport_closed_form(ora, n_dust_sweeps):
+    """Uniform gas flow U e_x, rho = 1, a dust ratio mode Y = Y0 (1 + e sin(kx + th)).
+    With D4 the I4-based central difference, z = i (U dt / h) (20 sin kh - 2 sin 2kh)/16,
+    m Jacobi sweeps give Y^m = sum_{l<=m} (-z)^l Y^n and the conservative finish
+    rho_j^{n+1} = sum_{l<=m+1} (-z)^l rho_j^n, per step, exactly."""
+    n, k, th, U, dt, Y0, e = 16, 2, 0.4, 0.5, 0.1, 1e-3, 0.5
+    h, (x, y, z) = grid(n)
+    rho, u = uniform_state(n, (U, 0.0, 0.0))
+    rp = (Y0 * (1 + e * np.sin(k * x + th)))[None]
+    o = ora.Oracle(n, rho, u, rp, gamma=GAMMA, C_=10.0, mu=1e-3, tau_p=(0.3,), dt_fixed=dt,
+                   n_dust_sweeps=n_dust_sweeps, p_tol=1e-12)
+    zz = 1j * (U * dt / h) * (20 * math.sin(k * h) - 2 * math.sin(2 * k * h)) / 16
+    A = sum((-zz) ** l for l in range(n_dust_sweeps + 2))
+    for steps in (1, 2):
+        o.step(1)
+        want = Y0 * (1 + e * np.imag(A ** steps * np.exp(1j * (k * x + th))))
+        got = o.get(ora.RHO_P)[0]
+        assert np.max(np.abs(got - want)) < 1e-15, steps
+
+
+@pytest.mark.parametrize("n_corr", [1, 2, 3])
+def test_momentum_shear_wave_closed_form(ora, n_corr):
+    """rho = 1, u = (U, e sin(kx + th), 0): a transverse wave advected by U and
+    damped by mu, with no density or pressure response (div phi = 0 exactly).
+    Each Jacobi sweep, and each corrector's H/a_P, applies u <- c u^n + g u with
+    a_P = 1/dt + 6 mu/h^2, c = 1/(dt a_P),
+    g = (mu (2 cos kh + 4)/h^2 - i (U/h)(20 sin kh - 2 sin 2kh)/16) / a_P,
+    so after n_U + n_corr applications u_y = B u_y^n with
+    B = c (1 + g + ... + g^(M-1)) + g^M."""
+    n, k, th, U, e, mu, dt = 16, 1, 0.2, 0.5, 0.05, 0.02, 0.05
+    h, (x, y, z) = grid(n)
+    rho, u = uniform_state(n, (U, 0.0, 0.0))
+    u[1] = e * np.sin(k * x + th)
+    n_u = 4
+    o = ora.Oracle(n, rho, u, None, gamma=GAMMA, C_=10.0, mu=mu, dt_fixed=dt, n_corr=n_corr,
+                   n_mom_sweeps=n_u, p_tol=1e-10)
+    aP = 1 / dt + 6 * mu / h ** 2
+    c = (1 / dt) / aP
+    g = (mu * (2 * math.cos(k * h) + 4) / h ** 2
+         - 1j * (U / h) * (20 * math.sin(k * h) - 2 * math.sin(2 * k * h)) / 16) / aP
+    M = n_u + n_corr
+    B = c * sum(g ** l for l in range(M)) + g ** M
+    for steps in (1, 2):
+        st, info = o.step(1)
+        assert st == 0 and info[0]["pcg_iters"] == [0] * n_corr   # b = 0 exactly
+        uu = o.get(ora.U)
+        want = e * np.imag(B ** steps * np.exp(1j * (k * x + th)))
+        assert np.max(np.abs(uu[1] - want)) < 1e-15
+        assert np.max(np.abs(uu[0] - U)) < 1e-15
+        assert np.max(np.abs(uu[2])) == 0.0
+        assert np.max(np.abs(o.get(ora.RHO) - 1.0)) == 0.0
+
+
+def test_acoustic_period(ora):
+    """A standing density wave rho = 1 + e cos x at rest oscillates with period
+    2 pi / (c k), c^2 = gamma C rho^(gamma-1) (the barotropic closure p = C rho^gamma,
+    second footnote).  Within 1.5% at 16^3 (a wrong gamma or C moves it by >10%)."""
+    n, e, dt = 16, 1e-4, 0.02
+    h, (x, y, z) = grid(n)
+    C = 1.0 / GAMMA           # c = 1
+    rho = 1 + e * np.cos(x)
+    u = np.zeros((3, n, n, n))
+    o = ora.Oracle(n, rho, u, None, gamma=GAMMA, C_=C, mu=0.0, dt_fixed=dt, p_tol=1e-12)
+    amps, ts = [], []
+    for _ in range(int(7.0 / dt)):
+        o.step(1)
+        amps.append(np.mean((o.get(ora.RHO) - 1) * np.cos(x)) * 2 / e)
+        ts.append(o.t)
+    amps, ts = np.array(amps), np.array(ts)
+    zc = [ts[i - 1] - amps[i - 1] * (ts[i] - ts[i - 1]) / (amps[i] - amps[i - 1])
+          for i in range(1, len(amps)) if amps[i - 1] * amps[i] < 0]
+    period = 2 * np.mean(np.diff(zc))
+    assert abs(period / (2 * math.pi) - 1) < 0.015, period
+
+
+def test_taylor_green_viscous_decay(ora):
+    """2D Taylor-Green vortex at Mach 0.05, nu = 0.01, 32^3: KE decays as
+    exp(-4 nu_d t) with nu_d = nu (2 - 2 cos h)/h^2 (the compact Laplacian's
+    symbol at k = 1); the fitted rate is within 0.3% of it (and within 1% of 4 nu)."""
+    n, nu, dt = 32, 0.01, 0.05
+    tg = taylor_green_case(n=n, mach=0.05, nu=nu)
+    o = ora.Oracle(n, tg["rho"], tg["u"], None, gamma=tg["gamma"], C_=tg["C"], mu=tg["mu"],
+                   dt_fixed=dt, p_tol=1e-12)
+    ke, ts = [o.stats()["ke"]], [0.0]
+    for _ in range(20):
+        o.step(1)
+        ke.append(o.stats()["ke"])
+        ts.append(o.t)
+    ts, ke = np.array(ts[5:]), np.log(np.array(ke[5:]))
+    rate = -np.polyfit(ts, ke, 1)[0]
+    h = 2 * math.pi / n
+    want = 4 * nu * (2 - 2 * math.cos(h)) / h ** 2
+    assert abs(rate / want - 1) < 3e-3, (rate, want)
+    assert abs(rate / (4 * nu) - 1) < 1e-2
+
+
+# ---------------------------------------------------------------- invariants
+@pytest.fixture(scope="module")
+def hit16():
+    return make_hit_case(16, 7, mach=0.2, stokes=(0.1, 0.5))
+
+
+def test_mass_conservation(ora, hit16):
+    """Gas and every particle class keep their total mass to round-off (flux form)."""
+    o = ora.Oracle.from_case(hit16, p_tol=1e-8)
+    s0 = o.stats()
+    st, info = o.step(20)
+    assert st == 0
+    for i in info:
+        assert abs(i["mass_gas"] / s0["mass_gas"] - 1) < 1e-13
+        for c in range(2):
+            assert abs(i["mass_p"][c] / s0["mass_p"][c] - 1) < 1e-13
+
+
+def test_dusty_gas_limit(ora, hit16):
+    """tau_p = 0 (Marble's dusty gas, the zero-order model of the third footnote)
+    with a uniform mass ratio keeps rho_j = ratio * rho every step; and the
+    first-order model departs from it linearly in tau_p."""
+    case = hit16
+    ratio = case.rho_p[0][0, 0, 0] / case.rho[0, 0, 0]
+    o = ora.Oracle(case.n, case.rho, case.u, case.rho_p[:1], gamma=case.gamma, C_=case.C,
+                   mu=case.mu, tau_p=(0.0,), p_tol=1e-8)
+    for _ in range(5):
+        o.step(1)
+        rp, r = o.get(ora.RHO_P)[0], o.get(ora.RHO)
+        assert np.max(np.abs(rp / (ratio * r) - 1)) < 1e-13
+    # slope 1 in tau after one step
+    dev = []
+    for tau in (0.0, 0.02, 0.01):
+        o = ora.Oracle(case.n, case.rho, case.u, case.rho_p[:1], gamma=case.gamma, C_=case.C,
+                       mu=case.mu, tau_p=(tau,), p_tol=1e-10)
+        o.step(1)
+        dev.append(o.get(ora.RHO_P)[0])
+    d1 = np.max(np.abs(dev[1] - dev[0]))
+    d2 = np.max(np.abs(dev[2] - dev[0]))
+    assert d1 > 0 and abs(d1 / d2 - 2) < 0.02
+
+
+def test_free_stream(ora):
+    """Uniform flow of uniform density is an exact discrete steady state."""
+    n = 8
+    U = (0.3, -0.2, 0.1)
+    rho, u = uniform_state(n, U)
+    rp = (1e-3 * rho)[None]
+    o = ora.Oracle(n, rho, u, rp, gamma=GAMMA, C_=20.0, mu=1e-3, tau_p=(0.05,), p_tol=1e-10,
+                   dt_max=0.1)
+    st, info = o.step(3)
+    assert st == 0
+    uu = o.get(ora.U)
+    for d in range(3):
+        assert np.max(np.abs(uu[d] - U[d])) < 1e-14
+    assert np.max(np.abs(o.get(ora.RHO) - 1)) < 1e-14
+    assert np.max(np.abs(o.get(ora.RHO_P)[0] - 1e-3)) < 1e-17
+
+
+def test_rest_state_bitwise(ora):
+    n = 8
+    rho, u = uniform_state(n)
+    rp = (2e-3 * rho)[None]
+    o = ora.Oracle(n, rho, u, rp, gamma=GAMMA, C_=20.0, mu=1e-3, tau_p=(0.05,), dt_fixed=0.1)
+    st, info = o.step(3)
+    assert st == 0 and info[-1]["pcg_iters"] == [0, 0]
+    assert np.array_equal(o.get(ora.RHO), rho)
+    assert np.array_equal(o.get(ora.U), u)
+    assert np.array_equal(o.get(ora.RHO_P)[0], rp[0])
+    assert np.array_equal(o.get(ora.PHI), np.zeros((3, n, n, n)))
+
+
+def test_adaptive_dt_needs_a_bound_at_rest(ora):
+    """At rest the convective Courant rate is zero; without dt_fixed or dt_max the
+    adaptive step is undefined and the step is rejected."""
+    n = 8
+    rho, u = uniform_state(n)
+    o = ora.Oracle(n, rho, u, None, gamma=GAMMA, C_=20.0)
+    st, _ = o.step(1)
+    assert st == ora.ERR_INVALID
+
+
+def test_translation_equivariance(ora, hit16):
+    case = hit16
+    sh = (1, 2, 3)      # cells along x, y, z
+
+    def roll(a):
+        return np.roll(a, shift=(sh[2], sh[1], sh[0]), axis=(-3, -2, -1))
+
+    o1 = ora.Oracle.from_case(case, p_tol=1e-10)
+    o2 = ora.Oracle(case.n, roll(case.rho), roll(case.u), roll(case.rho_p), gamma=case.gamma,
+                    C_=case.C, mu=case.mu, tau_p=case.tau_p, p_tol=1e-10)
+    o1.step(2)
+    o2.step(2)
+    for f in (ora.RHO, ora.U, ora.PHI, ora.RHO_P):
+        a, b = roll(o1.get(f)), o2.get(f)
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+
+
+def test_reflection_equivariance(ora, hit16):
+    """x -> -x with u_x -> -u_x maps a solution to a solution."""
+    case = hit16
+
+    def refl_cells(a):
+        return a[..., ::-1].copy()
+
+    u_r = refl_cells(case.u)
+    u_r[0] *= -1
+    o1 = ora.Oracle.from_case(case, p_tol=1e-10)
+    o2 = ora.Oracle(case.n, refl_cells(case.rho), u_r, refl_cells(case.rho_p), gamma=case.gamma,
+                    C_=case.C, mu=case.mu, tau_p=case.tau_p, p_tol=1e-10)
+    o1.step(2)
+    o2.step(2)
+    r1, r2 = o1.get(ora.RHO), o2.get(ora.RHO)
+    assert np.max(np.abs(refl_cells(r1) - r2)) <= 1e-12
+    u1, u2 = o1.get(ora.U), o2.get(ora.U)
+    u1r = refl_cells(u1)
+    u1r[0] *= -1
+    assert np.max(np.abs(u1r - u2)) <= 1e-12 * np.max(np.abs(u1))
+    p1, p2 = o1.get(ora.PHI), o2.get(ora.PHI)
+    # an x-face P+1/2 maps to the x-face of cell n-2-i
+    px = -np.roll(p1[0][..., ::-1], -1, axis=-1)
+    assert np.max(np.abs(px - p2[0])) <= 1e-12 * np.max(np.abs(p1))
+    rp1, rp2 = o1.get(ora.RHO_P), o2.get(ora.RHO_P)
+    assert np.max(np.abs(refl_cells(rp1) - rp2)) <= 1e-12 * np.max(np.abs(rp1))
+
+
+def test_determinism(ora, hit16):
+    runs = []
+    for _ in range(2):
+        o = ora.Oracle.from_case(hit16, p_tol=1e-8)
+        o.step(3)
+        runs.append([o.get(f) for f in (ora.RHO, ora.U, ora.PHI, ora.RHO_P)])
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
+def test_corrector_newton_fixed_point(ora, hit16):
+    """Repeating the corrector drives the continuity defect b towards zero: each
+    pass re-linearises the closure at the last density and re-evaluates H(u) at
+    the last velocity, a contraction (about 0.2 per pass here), so the nonlinear
+    step equations are solved in the limit."""
+    o = ora.Oracle.from_case(hit16, n_corr=6, p_tol=1e-13, capture=True)
+    o.step(1)
+    nb = [np.linalg.norm(o.get(ora.SYS_B, corr=c)) for c in range(6)]
+    assert all(nb[c + 1] < 0.3 * nb[c] for c in range(5)), nb
+    assert nb[5] < 1e-4 * nb[0], nb
+
+
+def test_total_energy_non_increasing(ora, hit16):
+    """KE + <C rho^gamma/(gamma-1)> does not grow with nu > 0 (soft pin: the
+    backward-Euler steps are dissipative)."""
+    o = ora.Oracle.from_case(hit16, p_tol=1e-10)
+    case = hit16
+
+    def energy():
+        s = o.stats()
+        r = o.get(ora.RHO)
+        return s["ke"] + np.mean(case.C * r ** case.gamma / (case.gamma - 1))
+    e = [energy()]
+    for _ in range(10):
+        o.step(1)
+        e.append(energy())
+    assert all(e[i + 1] <= e[i] * (1 + 1e-14) for i in range(10)), np.diff(e)
+    assert e[-1] < e[0]
+
+
+def test_stats_definitions_on_known_field(ora):
+    """Statistics of an analytic field: u = (sin y, 0, 0), rho = 1, one class
+    rho_j = 1 + 0.5 cos x.  KE = 1/4, <|curl u|^2/2> = S(h)^2 / 4 with the Gauss-I4
+    symbol S, density r.m.s. 0, concentration variance 1/8."""
+    n = 16
+    h, (x, y, z) = grid(n)
+    rho = np.ones((n, n, n))
+    u = np.stack([np.sin(y), np.zeros_like(y), np.zeros_like(y)])
+    rp = (1 + 0.5 * np.cos(x))[None]
+    o = ora.Oracle(n, rho, u, rp, gamma=GAMMA, C_=5.0, tau_p=(0.1,))
+    s = o.stats()
+    S = (20 * math.sin(h) - 2 * math.sin(2 * h)) / (16 * h)
+    assert abs(s["ke"] - 0.25) < 1e-14
+    assert abs(s["enstrophy"] - S * S / 4) < 1e-13
+    assert s["rho_rms"] == 0.0
+    assert abs(s["conc_var"][0] - 0.125) < 1e-14
+    assert abs(s["mach_rms"] - math.sqrt(0.5) / math.sqrt(GAMMA * 5.0)) < 1e-14
+    assert abs(s["mass_gas"] - (2 * math.pi) ** 3) < 1e-11
+
+
+def test_predictor_solves_conservative_momentum(ora):
+    """With enough Jacobi sweeps the predictor's u* solves the backward-Euler
+    momentum balance written in conservation form,
+      (rho* u* - rho^n u^n)/dt + div(phi^n I4(u*)) + grad p(rho^n)
+          - mu Lap u* - (mu/3) grad(div u^n) = 0,
+    assembled here from the separately pinned operators.  The (9/16) div(phi)
+    terms that the split into a_P and N(u) adds to both sides cancel only if
+    they agree, so a mismatch between them fails this check."""
+    case = make_hit_case(16, 7, mach=0.2, stokes=())
+    o = ora.Oracle.from_case(case, n_mom_sweeps=60, capture=True, p_tol=1e-10)
+    h = 2 * math.pi / case.n
+    rho0, u0 = case.rho, case.u
+    phi0 = [ora.i4(rho0, d) * ora.i4(u0[d], d) * h * h for d in range(3)]
+    st, info = o.step(1)
+    dt = info[0]["dt"]
+    us = o.get(ora.SYS_USTAR)
+    rhos = rho0 - dt * ora.div_flux(phi0)
+    gp = ora.grad(case.C * rho0 ** case.gamma)
+    gdu = ora.grad(ora.div_vel(u0))
+    scale = np.max(np.abs(rho0 * u0 / dt))
+    for d in range(3):
+        conv = ora.div_flux([phi0[e] * ora.i4(us[d], e) for e in range(3)])
+        r = ((rhos * us[d] - rho0 * u0[d]) / dt + conv + gp[d] - case.mu * ora.lap(us[d])
+             - case.mu / 3 * gdu[d])
+        assert np.max(np.abs(r)) < 1e-13 * scale
