@@ -339,3 +339,71 @@ def test_predictor_solves_conservative_momentum(ora):
         r = ((rhos * us[d] - rho0 * u0[d]) / dt + conv + gp[d] - case.mu * ora.lap(us[d])
              - case.mu / 3 * gdu[d])
         assert np.max(np.abs(r)) < 1e-13 * scale
+
+
+def test_drift_expels_dust_from_vortex_cores(ora):
+    """First-order drift u_p - u = -tau Du/Dt (the Equilibrium-Eulerian model of
+    the Results section).  In a Taylor-Green vortex Du/Dt ~ (u.grad)u =
+    (sin 2x, sin 2y, 0)/2, so after one step the dust gains
+    rho_j(tau) - rho_j(0) ~ Y tau dt (cos 2x + cos 2y): it leaves the vortex
+    cores (cos 2x + cos 2y = -2) for the strain regions, the preferential
+    concentration the paper says the model captures."""
+    n, dt, tau, Y0 = 32, 0.01, 0.02, 1e-3
+    tg = taylor_green_case(n=n, mach=0.05, nu=1e-3)
+    h, (x, y, z) = grid(n)
+    out = []
+    for t in (0.0, tau):
+        rp = (Y0 * tg["rho"])[None]
+        o = ora.Oracle(n, tg["rho"], tg["u"], rp, gamma=tg["gamma"], C_=tg["C"], mu=tg["mu"],
+                       tau_p=(t,), dt_fixed=dt, p_tol=1e-12)
+        o.step(1)
+        out.append(o.get(ora.RHO_P)[0])
+    d = out[1] - out[0]
+    shape = Y0 * tau * dt * (np.cos(2 * x) + np.cos(2 * y))
+    coef = np.sum(d * shape) / np.sum(shape * shape)
+    resid = np.linalg.norm(d - coef * shape) / np.linalg.norm(d)
+    assert 0.9 < coef < 1.1, coef
+    assert resid < 0.05, resid
+
+
+def test_dt_rule_closed_forms(ora):
+    """Uniform flow U e_x: sigma = sum_f |phi_f| / (2 rho V) = U / h, so
+    dt = cfl h / U on every step.  A decaying shear wave u_x = sin z with large
+    nu: u_x^{n+1} = B u_x^n (real B, the viscous closed form), so
+    sigma_2 = B sigma_1 and dt_2 = min(cfl / sigma_2, growth dt_1)."""
+    n, U, cfl = 8, 0.7, 0.5
+    h, (x, y, z) = grid(n)
+    rho, u = uniform_state(n, (U, 0.0, 0.0))
+    o = ora.Oracle(n, rho, u, None, gamma=GAMMA, C_=10.0, mu=1e-3, cfl=cfl, p_tol=1e-10)
+    st, info = o.step(2)
+    for i in info:
+        assert abs(i["dt"] - cfl * h / U) < 1e-15
+    for nu, growth in ((2.0, 1.2), (0.05, 1.2), (2.0, 3.0)):
+        rho, u = uniform_state(n)
+        u[0] = np.sin(z)
+        o = ora.Oracle(n, rho, u, None, gamma=GAMMA, C_=10.0, mu=nu, cfl=cfl, dt_growth=growth,
+                       p_tol=1e-12)
+        st, info = o.step(2)
+        sig1 = np.max(np.abs(np.sin(z))) / h
+        dt1 = cfl / sig1
+        assert abs(info[0]["dt"] - dt1) < 1e-14
+        aP = 1 / dt1 + 6 * nu / h ** 2
+        c = (1 / dt1) / aP
+        g = nu * (2 * math.cos(h) + 4) / h ** 2 / aP
+        B = c * sum(g ** l for l in range(6)) + g ** 6
+        dt2 = min(cfl / (B * sig1), growth * dt1)
+        assert abs(info[1]["dt"] - dt2) < 1e-12 * dt2, (nu, growth, info[1]["dt"], dt2)
+
+
+def test_stats_with_variable_density(ora):
+    """KE weights |u|^2 by rho: rho = 1 + cos(2y)/2, u = (sin y, 0, 0) gives
+    KE = <rho sin^2 y>/2 = 3/16 and density r.m.s. sqrt(1/8)."""
+    n = 16
+    h, (x, y, z) = grid(n)
+    rho = 1 + 0.5 * np.cos(2 * y)
+    u = np.stack([np.sin(y), np.zeros_like(y), np.zeros_like(y)])
+    o = ora.Oracle(n, rho, u, None, gamma=GAMMA, C_=5.0)
+    s = o.stats()
+    assert abs(s["ke"] - 3 / 16) < 1e-14
+    assert abs(s["rho_rms"] - math.sqrt(1 / 8)) < 1e-14
+    assert abs(s["mach_rms"] - math.sqrt(0.5) / math.sqrt(GAMMA * 5.0)) < 1e-14
