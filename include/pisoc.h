@@ -1,0 +1,198 @@
+/* pisoc.h -- C ABI of the MI355X (gfx950) PISO step library.
+ *
+ * One time step of the fast-Eulerian model of Cerminara et al. (arXiv
+ * 1404.0959, Results section): a compressible gas with the barotropic closure
+ * p = C rho^gamma (second footnote), advanced by a collocated finite-volume PISO
+ * pressure-based scheme with fourth-order central face interpolation and an
+ * adaptive time step, carrying K dust classes in the Equilibrium-Eulerian model
+ * (particle velocity u_p = u - tau_p Du/Dt, first order in the Stokes number;
+ * tau_p = 0 is Marble's dusty gas, third footnote), on the periodic cube
+ * [0, 2 pi)^3 with n cells per side (the paper's decaying homogeneous isotropic
+ * turbulence setting, Introduction and Fig. 1).
+ *
+ * Conventions for every entry point:
+ *  - Cell arrays hold n^3 doubles at offset i + n*(j + n*k) (x fastest).
+ *    Vector fields are structure-of-arrays: component d at offset d*n^3.
+ *    Face array d holds, at the offset of cell P, the value on the face
+ *    between P and P + e_d.
+ *  - Pointers named d_* are device pointers (hipMalloc'd or torch CUDA
+ *    tensors); h_* are host pointers.  The caller owns every buffer.  The
+ *    library never allocates device memory: all of its scratch lives in the
+ *    caller's workspace (see pisoc_workspace_bytes).  It allocates only the
+ *    small host context and a few bytes of pinned host memory for status.
+ *  - Work is enqueued on the caller's HIP stream (hipStream_t passed as void*,
+ *    NULL = default stream).  Calls that return host-visible results
+ *    synchronise that stream before returning.
+ *  - Errors are status codes; no exception crosses the ABI.  Warnings
+ *    (status > 0) still advance the state; errors (status < 0) leave the state
+ *    at the last completed step.  pisoc_last_error gives a message.
+ */
+#ifndef PISOC_H
+#define PISOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PISOC_MAX_CLASSES 8
+#define PISOC_MAX_CORR 4
+#define PISOC_MIN_N 8
+#define PISOC_MAX_N 1024
+
+typedef struct pisoc_ctx pisoc_ctx;
+
+typedef enum {
+    PISOC_OK = 0,
+    PISOC_WARN_NOT_CONVERGED = 1, /* a pressure solve hit p_maxit (state advanced) */
+    PISOC_WARN_GUESS_FALLBACK = 2, /* learned guess rejected, zero guess used */
+    PISOC_ERR_INVALID = -1,        /* bad argument, or dt undefined/non-positive */
+    PISOC_ERR_HIP = -2,            /* a HIP runtime call failed */
+    PISOC_ERR_DIVERGED = -3,       /* non-finite or non-positive density; step rejected */
+    PISOC_ERR_WORKSPACE = -4       /* workspace missing, too small or misaligned */
+} pisoc_status;
+
+/* arithmetic of the step */
+enum {
+    PISOC_FP64 = 0,         /* every field and operation in FP64 */
+    PISOC_FP32_REFINED = 1  /* FP32 fields, stencils and inner CG; FP64 residual
+                               refinement of the pressure solve, FP64 reductions */
+};
+
+/* initial value of each pressure solve */
+enum {
+    PISOC_GUESS_ZERO = 0,   /* p' = 0 */
+    PISOC_GUESS_LEARNED = 1 /* 3D conv net prediction, with fallback to 0 */
+};
+
+/* step-info flag bits */
+enum {
+    PISOC_FLAG_PCG_MAXIT = 1,
+    PISOC_FLAG_NONFINITE = 2,
+    PISOC_FLAG_RHO_NONPOS = 4,
+    PISOC_FLAG_GUESS_FALLBACK = 8,
+    PISOC_FLAG_BAD_DT = 16
+};
+
+typedef struct {
+    int32_t n;                 /* cells per side, PISOC_MIN_N..PISOC_MAX_N */
+    int32_t n_classes;         /* dust classes, 0..PISOC_MAX_CLASSES */
+    double gamma, C, mu;       /* p = C rho^gamma; dynamic viscosity */
+    double tau_p[PISOC_MAX_CLASSES]; /* particle response times (>= 0) */
+    double cfl;                /* target convective Courant number */
+    double dt_growth;          /* dt <= dt_growth * previous dt */
+    double dt_fixed;           /* > 0: use this dt every step, else adaptive */
+    double dt_max;             /* > 0: upper bound of the adaptive dt */
+    int32_t n_corr;            /* PISO correctors, 1..PISOC_MAX_CORR */
+    int32_t n_mom_sweeps;      /* Jacobi sweeps of the momentum predictor (>= 1) */
+    int32_t n_dust_sweeps;     /* Jacobi sweeps of each dust class (>= 1) */
+    double p_tol;              /* stop each pressure solve at ||r||_2 <= p_tol ||b||_2 */
+    int32_t p_maxit;           /* CG iteration cap per solve */
+    int32_t precision;         /* PISOC_FP64 or PISOC_FP32_REFINED */
+    int32_t guess;             /* PISOC_GUESS_ZERO or PISOC_GUESS_LEARNED */
+    const void* d_guess_weights; /* learned guess: device pointer to PISOC_GUESS_NWEIGHTS
+                                    floats (layer-major, see pisoc_guess_apply) */
+    double inner_tol;          /* FP32_REFINED: relative tolerance of each inner FP32 solve */
+    int32_t max_refine;        /* FP32_REFINED: cap on FP64 refinement rounds per solve */
+    int32_t capture;           /* != 0: keep corrector-1 pressure system of the last step
+                                  (b, p', p0, diag) for pisoc_fields */
+} pisoc_params;
+
+typedef struct {
+    double t, dt, courant;           /* time after the step, dt, sigma*dt */
+    int32_t pcg_iters[PISOC_MAX_CORR]; /* CG iterations per corrector (all rounds) */
+    double pcg_relres[PISOC_MAX_CORR]; /* final ||r||/||b|| per corrector */
+    int32_t refinements[PISOC_MAX_CORR]; /* FP64 refinement rounds (FP32_REFINED) */
+    int32_t flags;                   /* PISOC_FLAG_* */
+    double mass_gas;                 /* sum rho V after the step */
+    double mass_p[PISOC_MAX_CLASSES];/* sum rho_j V after the step */
+} pisoc_step_info;
+
+typedef struct {
+    double ke;        /* <rho |u|^2 / 2> */
+    double enstrophy; /* <|curl u|^2 / 2>, Gauss-I4 derivatives */
+    double rho_rms;   /* sqrt(<(rho - <rho>)^2>) / <rho> */
+    double mach_rms;  /* sqrt(<|u|^2>) / c0, c0^2 = gamma C <rho>^(gamma-1) */
+    double mass_gas;  /* sum rho V */
+    double conc_var[PISOC_MAX_CLASSES]; /* <(rho_j / <rho_j> - 1)^2> */
+    double mass_p[PISOC_MAX_CLASSES];   /* sum rho_j V */
+} pisoc_stats;
+
+/* field selectors for pisoc_fields (bit mask) */
+enum {
+    PISOC_FIELD_RHO = 1u << 0,      /* n^3 */
+    PISOC_FIELD_U = 1u << 1,        /* 3 n^3 */
+    PISOC_FIELD_PHI = 1u << 2,      /* 3 n^3 face mass fluxes */
+    PISOC_FIELD_RHO_P = 1u << 3,    /* n_classes n^3 */
+    PISOC_FIELD_P = 1u << 4,        /* n^3, C rho^gamma */
+    PISOC_FIELD_PSOLVE_B = 1u << 5, /* captured: right-hand side b (needs capture) */
+    PISOC_FIELD_PSOLVE_X = 1u << 6, /* captured: solution p' */
+    PISOC_FIELD_P_PREV = 1u << 7,   /* captured: p(rho) at the corrector's start */
+    PISOC_FIELD_PSOLVE_DIAG = 1u << 8 /* captured: diagonal of the pressure operator */
+};
+
+/* Bytes of device workspace pisoc_init needs for these parameters (0 if the
+ * parameters are invalid).  The workspace must be 256-byte aligned. */
+size_t pisoc_workspace_bytes(const pisoc_params* prm);
+
+/* Validate prm, lay out the workspace, convert the initial state and compute
+ * the initial face mass fluxes phi = I4(rho) I4(u_d) A.
+ * d_rho: n^3 FP64, d_u: 3 n^3 FP64 (SoA), d_rho_p: n_classes n^3 FP64 dust bulk
+ * densities (may be NULL when n_classes = 0).  The inputs are copied; the
+ * caller may free them afterwards.  On success *out receives a context that
+ * stays bound to d_workspace and hip_stream until pisoc_destroy. */
+pisoc_status pisoc_init(const pisoc_params* prm, void* d_workspace, size_t ws_bytes,
+                        const double* d_rho, const double* d_u, const double* d_rho_p,
+                        void* hip_stream, pisoc_ctx** out);
+
+/* Advance n_steps time steps.  h_info (host, may be NULL) receives one record
+ * per completed step.  Synchronises the stream before returning.  On an error
+ * the state stays at the last completed step and the number of completed steps
+ * is available from pisoc_steps_done. */
+pisoc_status pisoc_step(pisoc_ctx* ctx, int32_t n_steps, pisoc_step_info* h_info);
+
+/* Copy selected fields out as FP64, one destination per set bit of `which`, in
+ * increasing bit order (d_dst[0] for the lowest set bit).  Asynchronous. */
+pisoc_status pisoc_fields(pisoc_ctx* ctx, uint32_t which, double* const* d_dst);
+
+/* Volume statistics of the current state (FP64 reductions; synchronises). */
+pisoc_status pisoc_get_stats(pisoc_ctx* ctx, pisoc_stats* h_out);
+
+/* Simulated time and completed steps since init. */
+double pisoc_time(const pisoc_ctx* ctx);
+int64_t pisoc_steps_done(const pisoc_ctx* ctx);
+
+void pisoc_destroy(pisoc_ctx* ctx);
+const char* pisoc_last_error(const pisoc_ctx* ctx);
+const char* pisoc_status_string(pisoc_status st);
+
+/* ---- the pressure (Helmholtz) equation on its own -------------------------
+ * The operator of each PISO corrector (Results section: PISO with fourth-order
+ * central interpolation):
+ *   (M x)_P = psidt_P x_P + (1/h^2) sum_{faces f of P} K_f (x_P - x_nb(f)),
+ *   K_f = I4(w) on face f,  h = 2 pi / n,
+ * with cell fields psidt = psi/dt > 0 and w = rho/a_P > 0.  M is symmetric
+ * positive definite when every K_f > 0. */
+
+/* y = M x.  All arrays n^3 FP64 on the device.  Asynchronous. */
+pisoc_status pisoc_helm_apply(int32_t n, const double* d_psidt, const double* d_w,
+                              const double* d_x, double* d_y, void* hip_stream);
+
+/* Workspace for pisoc_helm_solve. */
+size_t pisoc_helm_workspace_bytes(int32_t n);
+
+/* Jacobi-preconditioned CG on M x = b from the x passed in (d_x is input and
+ * output).  Stops when ||r||_2 <= tol ||b||_2 or after maxit iterations
+ * (PISOC_WARN_NOT_CONVERGED).  *iters and *relres (host) receive the count
+ * and ||r||/||b||.  Synchronises. */
+pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_w,
+                              const double* d_b, double* d_x, double tol, int32_t maxit,
+                              void* d_workspace, size_t ws_bytes, void* hip_stream,
+                              int32_t* iters, double* relres);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,185 @@
+// device.hpp -- device-side building blocks shared by the PISO kernels:
+// grid geometry, periodic neighbour indexing, the fourth-order face
+// interpolation, and deterministic grid-wide reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace pisoc {
+
+constexpr int kBlock = 256;       // threads per block of every field kernel
+constexpr int kMaxRed = 8;        // values per grid reduction
+constexpr int kMaxCorr = 4;
+constexpr int kMaxClasses = 8;
+constexpr int kIterInf = 0x7fffffff;
+
+// Constants of one grid and gas, passed by value to the kernels.
+struct Phys {
+    int n;
+    int cz;             // cells per thread along z
+    double h, inv_h, inv_h2, V, inv_V, A;
+    double gamma, C, mu;
+    double rho_ref, p_ref;  // reference state: rho and p are stored as deviations
+};
+
+// State of one pressure solve, kept on the device so that CG never returns to
+// the host between iterations.
+struct PcgState {
+    double bb;        // ||b||^2
+    double rz;        // r.z of the current iterate
+    double alpha, beta;
+    double rr;        // ||r||^2
+    double tol2;      // tol^2
+    int32_t it_stop;  // first iteration index that must not run (kIterInf: keep going)
+    int32_t maxit;
+    int32_t iters;
+    int32_t converged;
+};
+
+// Everything the host reads back after a batch of work.
+struct DevState {
+    double dt, dt_prev, sigma, t;
+    PcgState pcg;
+    int32_t flags;
+    int32_t pad0;
+    double mass_gas;   // sum rho V of the last step
+    double usq;        // sum |u|^2 of the last step
+    double rho_min;
+    double mass_p[kMaxClasses];
+    double red[kMaxRed];
+    uint32_t counter[4];
+};
+
+// Geometry of a launch: blocks of 64x4 (or 32x8) threads over x-y, each
+// thread walking `cz` consecutive cells along z.
+struct CellIdx {
+    int n, i, j, k;
+    __device__ inline size_t at(int di, int dj, int dk) const {
+        int a = i + di, b = j + dj, c = k + dk;
+        a = a < 0 ? a + n : (a >= n ? a - n : a);
+        b = b < 0 ? b + n : (b >= n ? b - n : b);
+        c = c < 0 ? c + n : (c >= n ? c - n : c);
+        return (size_t)a + (size_t)n * ((size_t)b + (size_t)n * (size_t)c);
+    }
+    // cell reached by s steps along axis d
+    __device__ inline size_t sh(int d, int s) const {
+        return d == 0 ? at(s, 0, 0) : (d == 1 ? at(0, s, 0) : at(0, 0, s));
+    }
+    __device__ inline size_t self() const {
+        return (size_t)i + (size_t)n * ((size_t)j + (size_t)n * (size_t)k);
+    }
+};
+
+// Fourth-order central interpolation onto face P + (s + 1/2) e_d:
+// weights (-1, 9, 9, -1)/16 on cells P+s-1 .. P+s+2 along d.
+template <typename T>
+__device__ inline T i4(const T* __restrict__ q, const CellIdx& c, int d, int s) {
+    T a = q[c.sh(d, s - 1)], b = q[c.sh(d, s)], e = q[c.sh(d, s + 1)], f = q[c.sh(d, s + 2)];
+    return (T(9) * (b + e) - (a + f)) * T(0.0625);
+}
+
+// Gauss-theorem cell derivative along d from I4 face values.
+template <typename T>
+__device__ inline T dgauss(const T* __restrict__ q, const CellIdx& c, int d, T inv_h) {
+    return (i4(q, c, d, 0) - i4(q, c, d, -1)) * inv_h;
+}
+
+__device__ inline int flat_tid() { return threadIdx.x + blockDim.x * threadIdx.y; }
+__device__ inline unsigned flat_bid() {
+    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+__device__ inline unsigned num_blocks() { return gridDim.x * gridDim.y * gridDim.z; }
+
+template <bool MAX>
+__device__ inline double combine(double a, double b) {
+    if constexpr (MAX) return a > b ? a : b;
+    else return a + b;
+}
+
+template <bool MAX>
+__device__ inline double wave_reduce(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = combine<MAX>(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+// Block reduction of NV values (256 threads = 4 waves); component c uses max
+// when bit c of MAXMASK is set, else a sum.  Result valid in thread 0.  The
+// order of operations is fixed, so the result is bitwise reproducible.
+template <int NV, unsigned MAXMASK>
+__device__ inline void block_reduce(double (&v)[NV], double* lds) {
+    const int tid = flat_tid();
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        double x = ((MAXMASK >> c) & 1u) ? wave_reduce<true>(v[c]) : wave_reduce<false>(v[c]);
+        if (lane == 0) lds[wave * NV + c] = x;
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            if ((MAXMASK >> c) & 1u)
+                v[c] = combine<true>(combine<true>(lds[c], lds[NV + c]),
+                                     combine<true>(lds[2 * NV + c], lds[3 * NV + c]));
+            else
+                v[c] = (lds[c] + lds[NV + c]) + (lds[2 * NV + c] + lds[3 * NV + c]);
+        }
+    }
+    __syncthreads();
+}
+
+// Grid-wide deterministic reduction.  Every block writes its partials; the
+// block that arrives last (atomic ticket) reduces all partials in block order
+// and returns true with the totals in v[] of thread 0.  `partials` needs
+// NV * num_blocks doubles.  The counter is reset for the next kernel.
+template <int NV, unsigned MAXMASK>
+__device__ inline bool grid_reduce(double (&v)[NV], double* partials, uint32_t* counter) {
+    __shared__ double lds[4 * NV];
+    __shared__ int last;
+    block_reduce<NV, MAXMASK>(v, lds);
+    const int tid = flat_tid();
+    const unsigned nb = num_blocks();
+    if (tid == 0) {
+        const unsigned bid = flat_bid();
+#pragma unroll
+        for (int c = 0; c < NV; ++c) partials[(size_t)c * nb + bid] = v[c];
+        __threadfence();
+        unsigned ticket = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+        last = (ticket == nb - 1);
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        const bool mx = (MAXMASK >> c) & 1u;
+        double acc = 0.0;
+        bool first = true;
+        for (unsigned b = tid; b < nb; b += kBlock) {
+            double x = __hip_atomic_load(&partials[(size_t)c * nb + b], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+            acc = first ? x : (mx ? combine<true>(acc, x) : acc + x);
+            first = false;
+        }
+        if (first) acc = mx ? -__builtin_inf() : 0.0;
+        v[c] = acc;
+    }
+    block_reduce<NV, MAXMASK>(v, lds);
+    if (tid == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
+// Pressure deviation p(rho) - p_ref for rho = rho_ref + r, written with
+// log1p/expm1 so that it stays accurate for small r in FP32.
+__device__ inline double pdev(double r, const Phys& ph) {
+    return ph.p_ref * expm1(ph.gamma * log1p(r / ph.rho_ref));
+}
+__device__ inline float pdev(float r, const Phys& ph) {
+    return (float)ph.p_ref * expm1f((float)ph.gamma * log1pf(r / (float)ph.rho_ref));
+}
+
+}  // namespace pisoc

@@ -1,0 +1,280 @@
+"""ctypes binding of the C ABI in ``include/pisoc.h`` (``libpisoc.so``).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels of
+the library.  PyTorch provides device memory (the workspace and the field
+buffers) and the HIP stream.  There is no CPU fallback: if the library is not
+built, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpisoc.so")
+
+MAX_CLASSES = 8
+MAX_CORR = 4
+
+OK, WARN_NOT_CONVERGED, WARN_GUESS_FALLBACK = 0, 1, 2
+ERR_INVALID, ERR_HIP, ERR_DIVERGED, ERR_WORKSPACE = -1, -2, -3, -4
+FP64, FP32_REFINED = 0, 1
+GUESS_ZERO, GUESS_LEARNED = 0, 1
+FLAG_PCG_MAXIT, FLAG_NONFINITE, FLAG_RHO_NONPOS, FLAG_GUESS_FALLBACK, FLAG_BAD_DT = 1, 2, 4, 8, 16
+
+FIELD_RHO, FIELD_U, FIELD_PHI, FIELD_RHO_P, FIELD_P = 1, 2, 4, 8, 16
+FIELD_PSOLVE_B, FIELD_PSOLVE_X, FIELD_P_PREV, FIELD_PSOLVE_DIAG = 32, 64, 128, 256
+
+EXPORTED = [
+    "pisoc_workspace_bytes", "pisoc_init", "pisoc_step", "pisoc_fields", "pisoc_get_stats",
+    "pisoc_time", "pisoc_steps_done", "pisoc_destroy", "pisoc_last_error", "pisoc_status_string",
+    "pisoc_helm_apply", "pisoc_helm_workspace_bytes", "pisoc_helm_solve",
+]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("n_classes", C.c_int32),
+        ("gamma", C.c_double), ("C", C.c_double), ("mu", C.c_double),
+        ("tau_p", C.c_double * MAX_CLASSES),
+        ("cfl", C.c_double), ("dt_growth", C.c_double), ("dt_fixed", C.c_double),
+        ("dt_max", C.c_double),
+        ("n_corr", C.c_int32), ("n_mom_sweeps", C.c_int32), ("n_dust_sweeps", C.c_int32),
+        ("p_tol", C.c_double), ("p_maxit", C.c_int32),
+        ("precision", C.c_int32), ("guess", C.c_int32),
+        ("d_guess_weights", C.c_void_p),
+        ("inner_tol", C.c_double), ("max_refine", C.c_int32),
+        ("capture", C.c_int32),
+    ]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [
+        ("t", C.c_double), ("dt", C.c_double), ("courant", C.c_double),
+        ("pcg_iters", C.c_int32 * MAX_CORR), ("pcg_relres", C.c_double * MAX_CORR),
+        ("refinements", C.c_int32 * MAX_CORR),
+        ("flags", C.c_int32), ("mass_gas", C.c_double),
+        ("mass_p", C.c_double * MAX_CLASSES),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("ke", C.c_double), ("enstrophy", C.c_double), ("rho_rms", C.c_double),
+        ("mach_rms", C.c_double), ("mass_gas", C.c_double),
+        ("conc_var", C.c_double * MAX_CLASSES), ("mass_p", C.c_double * MAX_CLASSES),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libpisoc.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1404_0959_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, f64, sz = C.c_void_p, C.c_int32, C.c_double, C.c_size_t
+    L.pisoc_workspace_bytes.argtypes = [C.POINTER(Params)]
+    L.pisoc_workspace_bytes.restype = sz
+    L.pisoc_init.argtypes = [C.POINTER(Params), vp, sz, vp, vp, vp, vp, C.POINTER(vp)]
+    L.pisoc_init.restype = C.c_int
+    L.pisoc_step.argtypes = [vp, i32, C.POINTER(StepInfo)]
+    L.pisoc_step.restype = C.c_int
+    L.pisoc_fields.argtypes = [vp, C.c_uint32, C.POINTER(vp)]
+    L.pisoc_fields.restype = C.c_int
+    L.pisoc_get_stats.argtypes = [vp, C.POINTER(Stats)]
+    L.pisoc_get_stats.restype = C.c_int
+    L.pisoc_time.argtypes = [vp]
+    L.pisoc_time.restype = f64
+    L.pisoc_steps_done.argtypes = [vp]
+    L.pisoc_steps_done.restype = C.c_int64
+    L.pisoc_destroy.argtypes = [vp]
+    L.pisoc_destroy.restype = None
+    L.pisoc_last_error.argtypes = [vp]
+    L.pisoc_last_error.restype = C.c_char_p
+    L.pisoc_status_string.argtypes = [C.c_int]
+    L.pisoc_status_string.restype = C.c_char_p
+    L.pisoc_helm_apply.argtypes = [i32, vp, vp, vp, vp, vp]
+    L.pisoc_helm_apply.restype = C.c_int
+    L.pisoc_helm_workspace_bytes.argtypes = [i32]
+    L.pisoc_helm_workspace_bytes.restype = sz
+    L.pisoc_helm_solve.argtypes = [i32, vp, vp, vp, vp, f64, i32, vp, sz, vp,
+                                   C.POINTER(i32), C.POINTER(f64)]
+    L.pisoc_helm_solve.restype = C.c_int
+    _lib = L
+    return L
+
+
+class PisocError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"pisoc status {status}: {msg}")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("pisoc needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream_ptr(torch, stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_params(n, *, gamma, C_, mu, tau_p=(), cfl=0.5, dt_growth=1.2, dt_fixed=0.0, dt_max=0.0,
+                n_corr=2, n_mom_sweeps=4, n_dust_sweeps=4, p_tol=1e-8, p_maxit=500,
+                precision=FP64, guess=GUESS_ZERO, guess_weights=None, inner_tol=1e-3,
+                max_refine=20, capture=False) -> Params:
+    p = Params()
+    p.n = n
+    p.n_classes = len(tau_p)
+    p.gamma, p.C, p.mu = gamma, C_, mu
+    for i, t in enumerate(tau_p):
+        p.tau_p[i] = t
+    p.cfl, p.dt_growth, p.dt_fixed, p.dt_max = cfl, dt_growth, dt_fixed, dt_max
+    p.n_corr, p.n_mom_sweeps, p.n_dust_sweeps = n_corr, n_mom_sweeps, n_dust_sweeps
+    p.p_tol, p.p_maxit = p_tol, p_maxit
+    p.precision, p.guess = precision, guess
+    p.d_guess_weights = guess_weights
+    p.inner_tol, p.max_refine = inner_tol, max_refine
+    p.capture = 1 if capture else 0
+    return p
+
+
+class Solver:
+    """One simulation on one GPU, bound to a workspace tensor and a stream."""
+
+    def __init__(self, n, rho, u, rho_p=None, *, device="cuda:0", stream=None, **kw):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.n = n
+        self.prm = make_params(n, **kw)
+        self.K = self.prm.n_classes
+        L = lib()
+        nbytes = L.pisoc_workspace_bytes(C.byref(self.prm))
+        if nbytes == 0:
+            raise PisocError(ERR_INVALID, "invalid parameters")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream
+        dev = self.device
+        rho_d = torch.as_tensor(rho, dtype=torch.float64, device=dev).contiguous()
+        u_d = torch.as_tensor(u, dtype=torch.float64, device=dev).contiguous()
+        if self.K:
+            rp_d = torch.as_tensor(rho_p, dtype=torch.float64, device=dev).contiguous()
+            rp_ptr = rp_d.data_ptr()
+        else:
+            rp_ptr = None
+        N = n ** 3
+        assert rho_d.numel() == N and u_d.numel() == 3 * N
+        h = C.c_void_p()
+        st = L.pisoc_init(C.byref(self.prm), self.ws.data_ptr(), nbytes, rho_d.data_ptr(),
+                          u_d.data_ptr(), rp_ptr, _stream_ptr(torch, stream), C.byref(h))
+        if st != OK:
+            raise PisocError(st, "pisoc_init failed")
+        self._h = h
+
+    @classmethod
+    def from_case(cls, case, **kw):
+        return cls(case.n, case.rho, case.u, case.rho_p, gamma=case.gamma, C_=case.C, mu=case.mu,
+                   tau_p=case.tau_p, **kw)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.pisoc_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def last_error(self) -> str:
+        return lib().pisoc_last_error(self._h).decode()
+
+    def step(self, n_steps=1, raise_on_error=True):
+        infos = (StepInfo * max(n_steps, 1))()
+        st = lib().pisoc_step(self._h, n_steps, infos)
+        if st < 0 and raise_on_error:
+            raise PisocError(st, self.last_error())
+        nc = self.prm.n_corr
+        done = n_steps if st >= 0 else None
+        out = []
+        for i in range(n_steps if done is None else done):
+            r = infos[i]
+            out.append(dict(t=r.t, dt=r.dt, courant=r.courant,
+                            pcg_iters=list(r.pcg_iters[:nc]), pcg_relres=list(r.pcg_relres[:nc]),
+                            refinements=list(r.refinements[:nc]), flags=r.flags,
+                            mass_gas=r.mass_gas, mass_p=list(r.mass_p[: self.K])))
+        return st, out
+
+    def fields(self, which):
+        """Return {bit: float64 tensor} for the requested field bits."""
+        torch = self.torch
+        n = self.n
+        shapes = {FIELD_RHO: (n, n, n), FIELD_U: (3, n, n, n), FIELD_PHI: (3, n, n, n),
+                  FIELD_RHO_P: (max(self.K, 1), n, n, n), FIELD_P: (n, n, n),
+                  FIELD_PSOLVE_B: (n, n, n), FIELD_PSOLVE_X: (n, n, n),
+                  FIELD_P_PREV: (n, n, n), FIELD_PSOLVE_DIAG: (n, n, n)}
+        bits = [b for b in sorted(shapes) if which & b]
+        outs = [torch.empty(shapes[b], dtype=torch.float64, device=self.device) for b in bits]
+        arr = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        st = lib().pisoc_fields(self._h, which, arr)
+        if st != OK:
+            raise PisocError(st, self.last_error())
+        torch.cuda.current_stream().synchronize() if self.stream is None else self.stream.synchronize()
+        res = dict(zip(bits, outs))
+        if FIELD_RHO_P in res:
+            res[FIELD_RHO_P] = res[FIELD_RHO_P][: self.K]
+        return res
+
+    def get(self, bit):
+        return self.fields(bit)[bit]
+
+    def stats(self):
+        s = Stats()
+        st = lib().pisoc_get_stats(self._h, C.byref(s))
+        if st != OK:
+            raise PisocError(st, self.last_error())
+        K = self.K
+        return dict(ke=s.ke, enstrophy=s.enstrophy, rho_rms=s.rho_rms, mach_rms=s.mach_rms,
+                    mass_gas=s.mass_gas, conc_var=list(s.conc_var[:K]), mass_p=list(s.mass_p[:K]))
+
+    @property
+    def t(self):
+        return lib().pisoc_time(self._h)
+
+
+def helm_apply(psidt, w, x, stream=None):
+    """y = M x with M the pressure operator (see pisoc.h).  Device FP64 tensors."""
+    torch = _torch()
+    n = x.shape[-1]
+    y = torch.empty_like(x)
+    st = lib().pisoc_helm_apply(n, psidt.data_ptr(), w.data_ptr(), x.data_ptr(), y.data_ptr(),
+                                _stream_ptr(torch, stream))
+    if st != OK:
+        raise PisocError(st, "pisoc_helm_apply")
+    return y
+
+
+def helm_solve(psidt, w, b, x0=None, tol=1e-10, maxit=1000, stream=None):
+    """Jacobi-PCG on M x = b; returns (x, iterations, relres, status)."""
+    torch = _torch()
+    n = b.shape[-1]
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    nbytes = lib().pisoc_helm_workspace_bytes(n)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+    it = C.c_int32(0)
+    rel = C.c_double(0.0)
+    st = lib().pisoc_helm_solve(n, psidt.data_ptr(), w.data_ptr(), b.data_ptr(), x.data_ptr(),
+                                tol, maxit, ws.data_ptr(), nbytes, _stream_ptr(torch, stream),
+                                C.byref(it), C.byref(rel))
+    if st < 0:
+        raise PisocError(st, "pisoc_helm_solve")
+    return x, it.value, rel.value, st
