@@ -168,6 +168,24 @@ void pisoc_destroy(pisoc_ctx* ctx);
 const char* pisoc_last_error(const pisoc_ctx* ctx);
 const char* pisoc_status_string(pisoc_status st);
 
+/* ---- per-kernel timing ----------------------------------------------------
+ * When enabled, every kernel launch of pisoc_step is bracketed by HIP events
+ * on the context's stream and attributed to its kernel class, together with
+ * its algorithmic HBM bytes (each field word the kernel must read or write
+ * once).  CG launches that return at once because the solve has converged are
+ * not counted.  Enabling resets the counters. */
+#define PISOC_MAX_KSTATS 24
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double ms;     /* summed event time of the counted launches */
+    double bytes;  /* summed algorithmic bytes of the counted launches */
+} pisoc_kernel_stat;
+
+pisoc_status pisoc_profile(pisoc_ctx* ctx, int32_t enable);
+/* Copies up to max entries (classes with launches > 0); returns the count. */
+int32_t pisoc_profile_read(const pisoc_ctx* ctx, pisoc_kernel_stat* h_out, int32_t max);
+
 /* ---- the pressure (Helmholtz) equation on its own -------------------------
  * The operator of each PISO corrector (Results section: PISO with fourth-order
  * central interpolation):

@@ -29,11 +29,10 @@ struct Phys {
 // the host between iterations.
 struct PcgState {
     double bb;        // ||b||^2
-    double rz;        // r.z of the current iterate
-    double alpha, beta;
-    double rr;        // ||r||^2
+    double rzh[2];    // r.z of iterate k in slot k & 1
+    double rr;        // ||r||^2 of the last checked iterate
     double tol2;      // tol^2
-    int32_t it_stop;  // first iteration index that must not run (kIterInf: keep going)
+    int32_t it_stop;  // iteration index at which the solve stopped (kIterInf: running)
     int32_t maxit;
     int32_t iters;
     int32_t converged;
@@ -81,6 +80,15 @@ __device__ inline T i4(const T* __restrict__ q, const CellIdx& c, int d, int s) 
     return (T(9) * (b + e) - (a + f)) * T(0.0625);
 }
 
+// I4 of T-stored values evaluated in the arithmetic of R (FP64 evaluation of
+// FP32-stored fields).
+template <typename R, typename T>
+__device__ inline R i4r(const T* __restrict__ q, const CellIdx& c, int d, int s) {
+    R a = (R)q[c.sh(d, s - 1)], b = (R)q[c.sh(d, s)], e = (R)q[c.sh(d, s + 1)],
+      f = (R)q[c.sh(d, s + 2)];
+    return (R(9) * (b + e) - (a + f)) * R(0.0625);
+}
+
 // Gauss-theorem cell derivative along d from I4 face values.
 template <typename T>
 __device__ inline T dgauss(const T* __restrict__ q, const CellIdx& c, int d, T inv_h) {
@@ -105,13 +113,15 @@ __device__ inline double wave_reduce(double v) {
     return v;
 }
 
-// Block reduction of NV values (256 threads = 4 waves); component c uses max
-// when bit c of MAXMASK is set, else a sum.  Result valid in thread 0.  The
-// order of operations is fixed, so the result is bitwise reproducible.
+// Block reduction of NV values over the block's waves (up to 16 waves of 64);
+// component c uses max when bit c of MAXMASK is set, else a sum.  Result valid
+// in thread 0.  The order of operations is fixed, so the result is bitwise
+// reproducible.
 template <int NV, unsigned MAXMASK>
 __device__ inline void block_reduce(double (&v)[NV], double* lds) {
     const int tid = flat_tid();
     const int lane = tid & 63, wave = tid >> 6;
+    const int nw = (blockDim.x * blockDim.y + 63) >> 6;
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
         double x = ((MAXMASK >> c) & 1u) ? wave_reduce<true>(v[c]) : wave_reduce<false>(v[c]);
@@ -121,56 +131,56 @@ __device__ inline void block_reduce(double (&v)[NV], double* lds) {
     if (tid == 0) {
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
-            if ((MAXMASK >> c) & 1u)
-                v[c] = combine<true>(combine<true>(lds[c], lds[NV + c]),
-                                     combine<true>(lds[2 * NV + c], lds[3 * NV + c]));
-            else
-                v[c] = (lds[c] + lds[NV + c]) + (lds[2 * NV + c] + lds[3 * NV + c]);
+            double acc = lds[c];
+            for (int w = 1; w < nw; ++w)
+                acc = ((MAXMASK >> c) & 1u) ? combine<true>(acc, lds[w * NV + c]) : acc + lds[w * NV + c];
+            v[c] = acc;
         }
     }
     __syncthreads();
 }
 
-// Grid-wide deterministic reduction.  Every block writes its partials; the
-// block that arrives last (atomic ticket) reduces all partials in block order
-// and returns true with the totals in v[] of thread 0.  `partials` needs
-// NV * num_blocks doubles.  The counter is reset for the next kernel.
+// Per-block partials of a grid-wide reduction: thread 0 writes the block's
+// totals to part[c * num_blocks + block].  No fence is needed: the partials
+// are consumed by a later kernel on the same stream.
 template <int NV, unsigned MAXMASK>
-__device__ inline bool grid_reduce(double (&v)[NV], double* partials, uint32_t* counter) {
-    __shared__ double lds[4 * NV];
-    __shared__ int last;
+__device__ inline void block_partials(double (&v)[NV], double* part) {
+    __shared__ double lds[16 * NV];
     block_reduce<NV, MAXMASK>(v, lds);
-    const int tid = flat_tid();
-    const unsigned nb = num_blocks();
-    if (tid == 0) {
-        const unsigned bid = flat_bid();
+    if (flat_tid() == 0) {
+        const unsigned nb = num_blocks(), bid = flat_bid();
 #pragma unroll
-        for (int c = 0; c < NV; ++c) partials[(size_t)c * nb + bid] = v[c];
-        __threadfence();
-        unsigned ticket = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-        last = (ticket == nb - 1);
+        for (int c = 0; c < NV; ++c) part[(size_t)c * nb + bid] = v[c];
     }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
+}
+
+// Totals of partials written by an earlier kernel with `nb` blocks.  Every
+// block of the calling kernel computes the same totals in the same order
+// (bitwise identical, deterministic); all threads receive them.
+template <int NV, unsigned MAXMASK>
+__device__ inline void reduce_partials(const double* __restrict__ part, unsigned nb,
+                                       double (&out)[NV]) {
+    __shared__ double lds[16 * NV];
+    __shared__ double tot[NV];
+    const int tid = flat_tid();
+    const int nthr = blockDim.x * blockDim.y;
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
         const bool mx = (MAXMASK >> c) & 1u;
-        double acc = 0.0;
-        bool first = true;
-        for (unsigned b = tid; b < nb; b += kBlock) {
-            double x = __hip_atomic_load(&partials[(size_t)c * nb + b], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-            acc = first ? x : (mx ? combine<true>(acc, x) : acc + x);
-            first = false;
+        double acc = mx ? -__builtin_inf() : 0.0;
+        for (unsigned b = tid; b < nb; b += nthr) {
+            const double x = part[(size_t)c * nb + b];
+            acc = mx ? (x > acc ? x : acc) : acc + x;
         }
-        if (first) acc = mx ? -__builtin_inf() : 0.0;
-        v[c] = acc;
+        out[c] = acc;
     }
-    block_reduce<NV, MAXMASK>(v, lds);
-    if (tid == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
+    block_reduce<NV, MAXMASK>(out, lds);
+    if (tid == 0)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) tot[c] = out[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NV; ++c) out[c] = tot[c];
 }
 
 // Pressure deviation p(rho) - p_ref for rho = rho_ref + r, written with

@@ -64,13 +64,11 @@ __global__ void __launch_bounds__(kBlock) k_init_phi(Phys ph, const T* __restric
 }
 
 // ---------------------------------------------------------------- time step
-// Convective Courant rate sigma = max_P sum_f |phi_f| / (2 rho_P V) and the
-// adaptive dt = min(cfl / sigma, growth * dt_prev, dt_max) (or dt_fixed).
+// Per-block maxima of the convective Courant rate
+// sigma_P = sum_f |phi_f| / (2 rho_P V); the next kernel turns them into dt.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_cfl(Phys ph, DevState* st, const T* __restrict__ r,
-                                                const T* __restrict__ phi, double* partials,
-                                                double dt_fixed, double cfl, double growth,
-                                                double dt_prev, double dt_max) {
+__global__ void __launch_bounds__(kBlock) k_cfl(Phys ph, const T* __restrict__ r,
+                                                const T* __restrict__ phi, double* part) {
     const size_t N = ncell(ph);
     double v[1] = {0.0};
     FOR_CELLS(ph)
@@ -81,32 +79,38 @@ __global__ void __launch_bounds__(kBlock) k_cfl(Phys ph, DevState* st, const T* 
     double s = f / (2.0 * (ph.rho_ref + (double)r[P]) * ph.V);
     v[0] = s > v[0] ? s : v[0];
     END_CELLS
-    if (grid_reduce<1, 1u>(v, partials, &st->counter[0]) && flat_tid() == 0) {
-        double sigma = v[0];
-        double dt;
-        if (dt_fixed > 0.0) {
-            dt = dt_fixed;
-        } else {
-            dt = sigma > 0.0 ? cfl / sigma : __builtin_inf();
-            if (growth * dt_prev < dt) dt = growth * dt_prev;
-            if (dt_max > 0.0 && dt_max < dt) dt = dt_max;
-        }
-        if (!(dt > 0.0) || !isfinite(dt)) st->flags |= 16;  // bad dt
-        st->sigma = sigma;
-        st->dt = dt;
-    }
+    block_partials<1, 1u>(v, part);
 }
 
-// Density predictor rho* = rho^n - dt div(phi^n); momentum diagonal
+// Adaptive time step dt = min(cfl / sigma, growth dt_prev, dt_max) (or
+// dt_fixed) from the Courant partials; density predictor
+// rho* = rho^n - dt div(phi^n); momentum diagonal
 // a_P = rho*/dt + (9/16) div(phi^n) + 6 mu / h^2; div u^n (Gauss-I4); p(rho^n).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_predict(Phys ph, const DevState* st,
+__global__ void __launch_bounds__(kBlock) k_predict(Phys ph, DevState* st, const double* part_cfl,
+                                                    unsigned nb, double dt_fixed, double cfl,
+                                                    double growth, double dt_prev, double dt_max,
                                                     const T* __restrict__ rn, const T* __restrict__ un,
                                                     const T* __restrict__ phi, T* __restrict__ rs,
                                                     T* __restrict__ aP, T* __restrict__ divu,
                                                     T* __restrict__ pn) {
     const size_t N = ncell(ph);
-    const T dt = (T)st->dt;
+    double sg[1];
+    reduce_partials<1, 1u>(part_cfl, nb, sg);
+    double dtd;
+    if (dt_fixed > 0.0) {
+        dtd = dt_fixed;
+    } else {
+        dtd = sg[0] > 0.0 ? cfl / sg[0] : __builtin_inf();
+        if (growth * dt_prev < dtd) dtd = growth * dt_prev;
+        if (dt_max > 0.0 && dt_max < dtd) dtd = dt_max;
+    }
+    if (flat_bid() == 0 && flat_tid() == 0) {
+        if (!(dtd > 0.0) || !isfinite(dtd)) st->flags |= 16;  // bad dt
+        st->sigma = sg[0];
+        st->dt = dtd;
+    }
+    const T dt = (T)dtd;
     const T inv_V = (T)ph.inv_V, inv_h = (T)ph.inv_h;
     const T diag_visc = (T)(6.0 * ph.mu * ph.inv_h2);
     FOR_CELLS(ph)
@@ -192,73 +196,152 @@ __global__ void __launch_bounds__(kBlock) k_mom_sweep(Phys ph, const T* __restri
 // cell's own faces, and the pressure system M p' = b with
 //   b = -[(rho_k - rho^n)/dt + div(phiH - K A snGrad p0)],  K = I4(w),
 //   diag(M) = psi/dt + sum K / h^2,  psi = rho/(gamma p) = 1/(gamma C rho^(gamma-1)).
-// Starts CG from x = 0: r = b, partial sums of b.b and b.(b/diag).
+// The continuity defect is evaluated in FP64 arithmetic whatever T is (it is
+// a small difference of large fluxes).  Starts CG from x = 0: r = b and
+// partial sums of b.(b/diag), b.b, b.b.  With b64 non-null (FP32 storage) the
+// FP64 defect is also kept, and the FP64 solution accumulator x64 zeroed.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_corr_rhs(
     Phys ph, DevState* st, const T* __restrict__ rn, const T* __restrict__ rk,
     const T* __restrict__ w, const T* __restrict__ hbya, const T* __restrict__ p0,
     T* __restrict__ phiH, T* __restrict__ rvec, T* __restrict__ x, T* __restrict__ diag,
-    double* partials, double* snap_b, double* snap_diag, double* snap_p0) {
+    double* part_u, double* snap_b, double* snap_diag, double* snap_p0, double* b64,
+    double* x64) {
     const size_t N = ncell(ph);
-    const T dt = (T)st->dt;
-    const T A = (T)ph.A, inv_V = (T)ph.inv_V, inv_h = (T)ph.inv_h, inv_h2 = (T)ph.inv_h2;
-    const T rref = (T)ph.rho_ref;
-    double v[2] = {0.0, 0.0};
+    const double dt = st->dt;
+    const double A = ph.A, inv_V = ph.inv_V, inv_h = ph.inv_h, inv_h2 = ph.inv_h2;
+    const double rref = ph.rho_ref;
+    double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
-    T divF = T(0), sumK = T(0);
-    const T p0P = p0[P];
+    double divF = 0.0, sumK = 0.0;
+    const double p0P = (double)p0[P];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
 #pragma unroll
         for (int s = -1; s <= 0; ++s) {
-            const T Kf = i4(w, c, d, s);
-            const T ph_f = (rref + i4(rk, c, d, s)) * i4(hbya + d * N, c, d, s) * A;
-            const T sn = (s == 0 ? (p0[c.sh(d, 1)] - p0P) : (p0P - p0[c.sh(d, -1)])) * inv_h;
-            const T F = ph_f - Kf * A * sn;
+            const double Kf = i4r<double>(w, c, d, s);
+            const double ph_f = (rref + i4r<double>(rk, c, d, s)) * i4r<double>(hbya + d * N, c, d, s) * A;
+            const double sn = (s == 0 ? ((double)p0[c.sh(d, 1)] - p0P)
+                                      : (p0P - (double)p0[c.sh(d, -1)])) * inv_h;
+            const double F = ph_f - Kf * A * sn;
             divF += s == 0 ? F : -F;
             sumK += Kf;
-            if (s == 0) phiH[d * N + P] = ph_f;
+            if (s == 0) phiH[d * N + P] = (T)ph_f;
         }
     }
-    const T b = -((rk[P] - rn[P]) / dt + divF * inv_V);
-    const T rho = rref + rk[P];
-    const T psidt = rho / ((T)ph.gamma * ((T)ph.p_ref + p0P)) / dt;
-    const T dg = psidt + sumK * inv_h2;
-    rvec[P] = b;
+    const double b = -(((double)rk[P] - (double)rn[P]) / dt + divF * inv_V);
+    const double rho = rref + (double)rk[P];
+    const double psidt = rho / (ph.gamma * (ph.p_ref + p0P)) / dt;
+    const T dgT = (T)(psidt + sumK * inv_h2);
+    const T bT = (T)b;
+    rvec[P] = bT;
     x[P] = T(0);
-    diag[P] = dg;
-    v[0] += (double)b * (double)b;
-    v[1] += (double)b * ((double)b / (double)dg);
+    diag[P] = dgT;
+    const double bd = (double)bT;
+    v[0] += bd * (bd / (double)dgT);
+    v[1] += b64 ? b * b : bd * bd;
+    v[2] += b64 ? b * b : bd * bd;
+    if (b64) {
+        b64[P] = b;
+        x64[P] = 0.0;
+    }
     if (snap_b) {
-        snap_b[P] = (double)b;
-        snap_diag[P] = (double)dg;
-        snap_p0[P] = ph.p_ref + (double)p0P;
+        snap_b[P] = b;
+        snap_diag[P] = (double)dgT;
+        snap_p0[P] = ph.p_ref + p0P;
     }
     END_CELLS
-    if (grid_reduce<2, 0u>(v, partials, &st->counter[0]) && flat_tid() == 0) {
-        PcgState& g = st->pcg;
-        g.bb = v[0];
-        g.rr = v[0];
-        g.rz = v[1];
-        g.iters = 0;
-        g.converged = v[0] <= g.tol2 * v[0] ? 1 : 0;
-        g.it_stop = g.converged ? 0 : kIterInf;
+    block_partials<3, 0u>(v, part_u);
+    if (flat_bid() == 0 && flat_tid() == 0) {
+        st->pcg.it_stop = kIterInf;
+        st->pcg.converged = 0;
+        st->pcg.iters = 0;
     }
 }
 
+// FP64 residual refinement (FP32 storage): accumulate the inner FP32
+// correction, x64_new = x64 + d, evaluate r64 = b64 - M x64_new in FP64
+// arithmetic (coefficients K = I4(w) and diag from their FP32 storage), and
+// set up the next inner solve's right-hand side float(r64) with partial sums
+// r.(r/diag), ||r64||^2, ||r64||^2 (the inner correction d is zeroed after).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
+                                                   const double* __restrict__ x64,
+                                                   const T* __restrict__ d, double* __restrict__ x64n,
+                                                   const double* __restrict__ b64,
+                                                   const T* __restrict__ w, const T* __restrict__ diag,
+                                                   T* __restrict__ r32, double* part_u) {
+    const double inv_h2 = ph.inv_h2;
+    double v[3] = {0.0, 0.0, 0.0};
+    FOR_CELLS(ph)
+    auto xn = [&](size_t Q) { return x64[Q] + (double)d[Q]; };
+    const double xP = xn(P);
+    double lap = 0.0, sumK = 0.0;
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) {
+        const double kp = i4r<double>(w, c, dd, 0), km = i4r<double>(w, c, dd, -1);
+        lap += kp * (xP - xn(c.sh(dd, 1))) + km * (xP - xn(c.sh(dd, -1)));
+        sumK += kp + km;
+    }
+    const double r = b64[P] - (((double)diag[P] - sumK * inv_h2) * xP + lap * inv_h2);
+    x64n[P] = xP;
+    const T rT = (T)r;
+    r32[P] = rT;
+    v[0] += (double)rT * ((double)rT / (double)diag[P]);
+    v[1] += r * r;
+    v[2] += r * r;
+    END_CELLS
+    block_partials<3, 0u>(v, part_u);
+    if (flat_bid() == 0 && flat_tid() == 0) {
+        st->pcg.it_stop = kIterInf;
+        st->pcg.converged = 0;
+        st->pcg.iters = 0;
+    }
+}
+
+// Zero a field (the inner correction) -- a kernel, not a memset, so that the
+// step can be captured in a graph.
+template <typename T>
+__global__ void k_zero(T* __restrict__ a, size_t count) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) a[i] = T(0);
+}
+
 // ---------------------------------------------------------------- CG
-// Iteration k, first half: direction p_k = z_k + beta_{k-1} p_{k-1} with
-// z = r / diag (recomputed on the stencil, not stored), q = M p_k with the
-// face coefficients K = I4(w) formed on the fly, partial sums of p_k.q, and
-// alpha_k = r.z / p.q in the last block.
+// Iteration k, first half.  Totals of the previous kernel's partials give
+// r_k.z_k, ||r_k||^2 (and ||b||^2 when k = 0); the solve stops here when
+// ||r_k||^2 <= tol^2 ||b||^2 or k = maxit (every block takes the same
+// decision).  Otherwise: direction p_k = z_k + beta_{k-1} p_{k-1} with
+// z = r / diag recomputed on the stencil (not stored), q = M p_k with the face
+// coefficients K = I4(w) formed on the fly, and partial sums of p_k.q.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_pcg_spmv(Phys ph, DevState* st, int k,
                                                      const T* __restrict__ r, const T* __restrict__ diag,
                                                      const T* __restrict__ w, const T* __restrict__ pold,
                                                      T* __restrict__ pnew, T* __restrict__ q,
-                                                     double* partials) {
+                                                     const double* part_u, double* part_s, unsigned nb,
+                                                     double tol2, int maxit) {
     if (k >= st->pcg.it_stop) return;
-    const T beta = k == 0 ? T(0) : (T)st->pcg.beta;
+    double t[3];
+    reduce_partials<3, 0u>(part_u, nb, t);
+    const double rz = t[0], rr = t[1];
+    const double bb = k == 0 ? t[2] : st->pcg.bb;
+    const bool conv = rr <= tol2 * bb;
+    const bool stop = conv || k >= maxit;
+    if (flat_bid() == 0 && flat_tid() == 0) {
+        PcgState& g = st->pcg;
+        g.rr = rr;
+        g.iters = k;
+        g.rzh[k & 1] = rz;
+        if (k == 0) g.bb = bb;
+        if (stop) {
+            g.it_stop = k;
+            g.converged = conv ? 1 : 0;
+        }
+    }
+    if (stop) return;
+    const T beta = k == 0 ? T(0) : (T)(rz / st->pcg.rzh[(k - 1) & 1]);
     const bool first = k == 0;
     const T inv_h2 = (T)ph.inv_h2;
     double v[1] = {0.0};
@@ -268,32 +351,158 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(Phys ph, DevState* st, int 
         return first ? z : z + beta * pold[Q];
     };
     const T pP = dir(P);
-    T off = T(0);
+    // difference form psi/dt p_P + sum K (p_P - p_nb) / h^2 (no cancellation
+    // between the diagonal and the neighbour sum for smooth p)
+    T lap = T(0), sumK = T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        off += i4(w, c, d, 0) * dir(c.sh(d, 1));
-        off += i4(w, c, d, -1) * dir(c.sh(d, -1));
+        const T kp = i4(w, c, d, 0), km = i4(w, c, d, -1);
+        lap += kp * (pP - dir(c.sh(d, 1))) + km * (pP - dir(c.sh(d, -1)));
+        sumK += kp + km;
     }
-    const T qP = diag[P] * pP - off * inv_h2;
+    const T qP = (diag[P] - sumK * inv_h2) * pP + lap * inv_h2;
     pnew[P] = pP;
     q[P] = qP;
     v[0] += (double)pP * (double)qP;
     END_CELLS
-    if (grid_reduce<1, 0u>(v, partials, &st->counter[0]) && flat_tid() == 0)
-        st->pcg.alpha = st->pcg.rz / v[0];
+    block_partials<1, 0u>(v, part_s);
 }
 
-// Iteration k, second half: x += alpha p, r -= alpha q, partial sums of
-// r.(r/diag) and r.r; the last block forms beta_k and tests
-// ||r||^2 <= tol^2 ||b||^2 (or k + 1 = maxit), which stops later launches.
+// Tiled form of the first half for n a multiple of 64 (and >= 128): a block
+// owns a 64 x 8 column tile and marches along z.  The face coefficients
+// K = I4(w) and the direction p = z + beta p_old are read once per cell from
+// HBM: the x-y neighbours of the current plane come from LDS tiles (halo 2 for
+// w, 1 for p), the z neighbours from per-thread register queues.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_pcg_update(Phys ph, DevState* st, int k,
+__global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
+    Phys ph, DevState* st, int k, const T* __restrict__ r, const T* __restrict__ diag,
+    const T* __restrict__ w, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ q,
+    const double* part_u, unsigned nb_u, double* part_s, double tol2, int maxit) {
+    if (k >= st->pcg.it_stop) return;
+    double t[3];
+    reduce_partials<3, 0u>(part_u, nb_u, t);
+    const double rz = t[0], rr = t[1];
+    const double bb = k == 0 ? t[2] : st->pcg.bb;
+    const bool conv = rr <= tol2 * bb;
+    const bool stop = conv || k >= maxit;
+    if (flat_bid() == 0 && flat_tid() == 0) {
+        PcgState& g = st->pcg;
+        g.rr = rr;
+        g.iters = k;
+        g.rzh[k & 1] = rz;
+        if (k == 0) g.bb = bb;
+        if (stop) {
+            g.it_stop = k;
+            g.converged = conv ? 1 : 0;
+        }
+    }
+    if (stop) return;
+    const T beta = k == 0 ? T(0) : (T)(rz / st->pcg.rzh[(k - 1) & 1]);
+    const bool first = k == 0;
+    const T inv_h2 = (T)ph.inv_h2;
+    const int n = ph.n, cz = ph.cz;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kTX * ty;
+    const int i0 = blockIdx.x * kTX, j0 = blockIdx.y * kTY;
+    const int k0 = blockIdx.z * cz;
+    const int k1 = k0 + cz < n ? k0 + cz : n;
+    const size_t nn = (size_t)n * n;
+    __shared__ T ws[kTY + 4][kTX + 4];
+    __shared__ T ps[kTY + 2][kTX + 2];
+    auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
+    auto dirv = [&](size_t Q) -> T {
+        const T zz = r[Q] / diag[Q];
+        return first ? zz : zz + beta * pold[Q];
+    };
+    const size_t col = (size_t)(i0 + tx) + (size_t)n * (j0 + ty);
+    T wq0 = w[col + nn * wr(k0 - 2)], wq1 = w[col + nn * wr(k0 - 1)], wq2 = w[col + nn * k0],
+      wq3 = w[col + nn * wr(k0 + 1)];
+    T pm = dirv(col + nn * wr(k0 - 1)), pc = dirv(col + nn * k0);
+    T dc = diag[col + nn * k0];
+    // this thread's halo cell, if any (same x-y position on every plane)
+    int hkind = 0, hy = 0, hx = 0;
+    size_t hoff = 0;
+    if (tid < 256) {            // w rows j0-2, j0-1, j0+8, j0+9
+        const int row = tid >> 6, x = tid & 63;
+        hy = row < 2 ? row : kTY + row;
+        hx = x + 2;
+        hoff = (size_t)(i0 + x) + (size_t)n * wr(j0 - 2 + hy);
+        hkind = 1;
+    } else if (tid < 288) {     // w columns i0-2, i0-1, i0+64, i0+65
+        const int t2 = tid - 256, c4 = t2 >> 3, y = t2 & 7;
+        hx = c4 < 2 ? c4 : kTX + c4;
+        hy = y + 2;
+        hoff = (size_t)wr(i0 - 2 + hx) + (size_t)n * (j0 + y);
+        hkind = 1;
+    } else if (tid < 416) {     // p rows j0-1, j0+8
+        const int t3 = tid - 288, row = t3 >> 6, x = t3 & 63;
+        hy = row == 0 ? 0 : kTY + 1;
+        hx = x + 1;
+        hoff = (size_t)(i0 + x) + (size_t)n * wr(j0 - 1 + hy);
+        hkind = 2;
+    } else if (tid < 432) {     // p columns i0-1, i0+64
+        const int t4 = tid - 416, c2 = t4 >> 3, y = t4 & 7;
+        hx = c2 == 0 ? 0 : kTX + 1;
+        hy = y + 1;
+        hoff = (size_t)wr(i0 - 1 + hx) + (size_t)n * (j0 + y);
+        hkind = 2;
+    }
+    double acc = 0.0;
+    for (int kk = k0; kk < k1; ++kk) {
+        const size_t pl = nn * (size_t)kk;
+        const T wq4 = w[col + nn * wr(kk + 2)];
+        const size_t Qn = col + nn * wr(kk + 1);
+        const T dn = diag[Qn];
+        const T pp = first ? r[Qn] / dn : r[Qn] / dn + beta * pold[Qn];
+        ws[ty + 2][tx + 2] = wq2;
+        ps[ty + 1][tx + 1] = pc;
+        if (hkind == 1) ws[hy][hx] = w[pl + hoff];
+        else if (hkind == 2) ps[hy][hx] = dirv(pl + hoff);
+        __syncthreads();
+        const T kxp = (T(9) * (ws[ty + 2][tx + 2] + ws[ty + 2][tx + 3]) -
+                       (ws[ty + 2][tx + 1] + ws[ty + 2][tx + 4])) * T(0.0625);
+        const T kxm = (T(9) * (ws[ty + 2][tx + 1] + ws[ty + 2][tx + 2]) -
+                       (ws[ty + 2][tx] + ws[ty + 2][tx + 3])) * T(0.0625);
+        const T kyp = (T(9) * (ws[ty + 2][tx + 2] + ws[ty + 3][tx + 2]) -
+                       (ws[ty + 1][tx + 2] + ws[ty + 4][tx + 2])) * T(0.0625);
+        const T kym = (T(9) * (ws[ty + 1][tx + 2] + ws[ty + 2][tx + 2]) -
+                       (ws[ty][tx + 2] + ws[ty + 3][tx + 2])) * T(0.0625);
+        const T kzp = (T(9) * (wq2 + wq3) - (wq1 + wq4)) * T(0.0625);
+        const T kzm = (T(9) * (wq1 + wq2) - (wq0 + wq3)) * T(0.0625);
+        const T lap = kxp * (pc - ps[ty + 1][tx + 2]) + kxm * (pc - ps[ty + 1][tx]) +
+                      kyp * (pc - ps[ty + 2][tx + 1]) + kym * (pc - ps[ty][tx + 1]) +
+                      kzp * (pc - pp) + kzm * (pc - pm);
+        const T sumK = kxp + kxm + kyp + kym + kzp + kzm;
+        const T qv = (dc - sumK * inv_h2) * pc + lap * inv_h2;
+        q[col + pl] = qv;
+        pnew[col + pl] = pc;
+        acc += (double)pc * (double)qv;
+        __syncthreads();
+        wq0 = wq1;
+        wq1 = wq2;
+        wq2 = wq3;
+        wq3 = wq4;
+        pm = pc;
+        pc = pp;
+        dc = dn;
+    }
+    double v[1] = {acc};
+    block_partials<1, 0u>(v, part_s);
+}
+
+// Iteration k, second half: alpha_k = r_k.z_k / p_k.q from the previous
+// kernel's partials, x += alpha p, r -= alpha q, and partial sums of
+// r.(r/diag) and r.r for the next first half.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pcg_update(Phys ph, const DevState* st, int k,
                                                        T* __restrict__ r, const T* __restrict__ q,
                                                        const T* __restrict__ diag, T* __restrict__ x,
-                                                       const T* __restrict__ p, double* partials) {
+                                                       const T* __restrict__ p, const double* part_s,
+                                                       double* part_u, unsigned nb_s) {
     if (k >= st->pcg.it_stop) return;
-    const T alpha = (T)st->pcg.alpha;
-    double v[2] = {0.0, 0.0};
+    double pq[1];
+    reduce_partials<1, 0u>(part_s, nb_s, pq);
+    const T alpha = (T)(st->pcg.rzh[k & 1] / pq[0]);
+    double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
     x[P] += alpha * p[P];
     const T rn = r[P] - alpha * q[P];
@@ -301,19 +510,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(Phys ph, DevState* st, in
     v[0] += (double)rn * ((double)rn / (double)diag[P]);
     v[1] += (double)rn * (double)rn;
     END_CELLS
-    if (grid_reduce<2, 0u>(v, partials, &st->counter[0]) && flat_tid() == 0) {
-        PcgState& g = st->pcg;
-        g.beta = v[0] / g.rz;
-        g.rz = v[0];
-        g.rr = v[1];
-        g.iters = k + 1;
-        if (v[1] <= g.tol2 * g.bb) {
-            g.converged = 1;
-            g.it_stop = k + 1;
-        } else if (k + 1 >= g.maxit) {
-            g.it_stop = k + 1;
-        }
-    }
+    block_partials<3, 0u>(v, part_u);
 }
 
 // y = M x for the stand-alone operator entry point (psi/dt given as a field).
@@ -341,7 +538,7 @@ __global__ void __launch_bounds__(kBlock) k_helm_start(Phys ph, DevState* st,
                                                        const T* __restrict__ psidt,
                                                        const T* __restrict__ w, const T* __restrict__ b,
                                                        const T* __restrict__ x, T* __restrict__ r,
-                                                       T* __restrict__ diag, double* partials) {
+                                                       T* __restrict__ diag, double* part_u) {
     const T inv_h2 = (T)ph.inv_h2;
     double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
@@ -357,18 +554,15 @@ __global__ void __launch_bounds__(kBlock) k_helm_start(Phys ph, DevState* st,
     const T rr = b[P] - (psidt[P] * xP + s * inv_h2);
     r[P] = rr;
     diag[P] = dg;
-    v[0] += (double)b[P] * (double)b[P];
-    v[1] += (double)rr * ((double)rr / (double)dg);
-    v[2] += (double)rr * (double)rr;
+    v[0] += (double)rr * ((double)rr / (double)dg);
+    v[1] += (double)rr * (double)rr;
+    v[2] += (double)b[P] * (double)b[P];
     END_CELLS
-    if (grid_reduce<3, 0u>(v, partials, &st->counter[0]) && flat_tid() == 0) {
-        PcgState& g = st->pcg;
-        g.bb = v[0];
-        g.rz = v[1];
-        g.rr = v[2];
-        g.iters = 0;
-        g.converged = v[2] <= g.tol2 * v[0] ? 1 : 0;
-        g.it_stop = g.converged ? 0 : kIterInf;
+    block_partials<3, 0u>(v, part_u);
+    if (flat_bid() == 0 && flat_tid() == 0) {
+        st->pcg.it_stop = kIterInf;
+        st->pcg.converged = 0;
+        st->pcg.iters = 0;
     }
 }
 
@@ -398,7 +592,7 @@ __global__ void __launch_bounds__(kBlock) k_corr_flux(Phys ph, const T* __restri
 // u = HbyA - grad(p)/a_P.  On the last corrector, partial sums for the mass
 // budget and the divergence checks (sum r, sum |u|^2, max(-rho)).
 template <typename T, bool LAST>
-__global__ void __launch_bounds__(kBlock) k_corr_update(Phys ph, DevState* st,
+__global__ void __launch_bounds__(kBlock) k_corr_update(Phys ph, const DevState* st,
                                                         const T* __restrict__ rn,
                                                         const T* __restrict__ phik,
                                                         const T* __restrict__ hbya,
@@ -430,15 +624,7 @@ __global__ void __launch_bounds__(kBlock) k_corr_update(Phys ph, DevState* st,
         v[2] = nrho > v[2] ? nrho : v[2];
     }
     END_CELLS
-    if (LAST) {
-        if (grid_reduce<3, 4u>(v, partials, &st->counter[0]) && flat_tid() == 0) {
-            st->mass_gas = (ph.rho_ref * (double)ncell(ph) + v[0]) * ph.V;
-            st->usq = v[1];
-            st->rho_min = -v[2];
-            if (!isfinite(v[0]) || !isfinite(v[1])) st->flags |= 2;
-            if (!(-v[2] > 0.0)) st->flags |= 4;
-        }
-    }
+    if (LAST) block_partials<3, 4u>(v, partials);
 }
 
 // ---------------------------------------------------------------- dust
@@ -517,7 +703,7 @@ __global__ void __launch_bounds__(kBlock) k_dust_faceflux(Phys ph, const T* __re
 
 // Conservative finish rho_j^{n+1} = rho_j^n - dt div(F); partial mass sum.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_dust_finish(Phys ph, DevState* st, int cls,
+__global__ void __launch_bounds__(kBlock) k_dust_finish(Phys ph, const DevState* st,
                                                         const T* __restrict__ rhoj,
                                                         const T* __restrict__ F, T* __restrict__ rhoj1,
                                                         double* partials) {
@@ -532,14 +718,13 @@ __global__ void __launch_bounds__(kBlock) k_dust_finish(Phys ph, DevState* st, i
     rhoj1[P] = out;
     v[0] += (double)out;
     END_CELLS
-    if (grid_reduce<1, 0u>(v, partials, &st->counter[0]) && flat_tid() == 0)
-        st->mass_p[cls] = v[0] * ph.V;
+    block_partials<1, 0u>(v, partials);
 }
 
 // ---------------------------------------------------------------- statistics
-// Sums of rho|u|^2/2, |curl u|^2/2 (Gauss-I4), |u|^2 and r into st->red[0..3].
+// Partial sums of rho|u|^2/2, |curl u|^2/2 (Gauss-I4), |u|^2 and r.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_stats_gas(Phys ph, DevState* st,
+__global__ void __launch_bounds__(kBlock) k_stats_gas(Phys ph,
                                                       const T* __restrict__ r,
                                                       const T* __restrict__ u, double* partials) {
     const size_t N = ncell(ph);
@@ -558,36 +743,86 @@ __global__ void __launch_bounds__(kBlock) k_stats_gas(Phys ph, DevState* st,
     v[2] += q;
     v[3] += (double)r[P];
     END_CELLS
-    if (grid_reduce<4, 0u>(v, partials, &st->counter[0]) && flat_tid() == 0)
-        for (int i = 0; i < 4; ++i) st->red[i] = v[i];
+    block_partials<4, 0u>(v, partials);
 }
 
-// st->red[slot] = sum (a x + b)^2 and st->red[slot+1] = sum x.
+// Partial sums of (a x + b)^2 and of x.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sum_affine_sq(Phys ph, DevState* st,
-                                                          const T* __restrict__ x, double a,
-                                                          double b, int slot, double* partials) {
+__global__ void __launch_bounds__(kBlock) k_sum_affine_sq(Phys ph, const T* __restrict__ x,
+                                                          double a, double b, double* partials) {
     double v[2] = {0.0, 0.0};
     FOR_CELLS(ph)
     const double y = a * (double)x[P] + b;
     v[0] += y * y;
     v[1] += (double)x[P];
     END_CELLS
-    if (grid_reduce<2, 0u>(v, partials, &st->counter[0]) && flat_tid() == 0) {
-        st->red[slot] = v[0];
-        st->red[slot + 1] = v[1];
+    block_partials<2, 0u>(v, partials);
+}
+
+// One block: totals of nv partial columns (sums) into dst[0..nv-1].
+__global__ void __launch_bounds__(kBlock) k_finalize_sums(const double* part, unsigned nb, int nv,
+                                                          double* dst) {
+    for (int c = 0; c < nv; ++c) {
+        double t[1];
+        reduce_partials<1, 0u>(part + (size_t)c * nb, nb, t);
+        if (flat_tid() == 0) dst[c] = t[0];
+    }
+}
+
+// One block at the end of a step: mass budget, divergence flags and the dust
+// class masses from the partials of the last corrector and the dust finish.
+__global__ void __launch_bounds__(kBlock) k_step_finish(Phys ph, DevState* st,
+                                                        const double* part_mass,
+                                                        const double* part_dust, int ncls,
+                                                        unsigned nb, size_t cls_stride) {
+    double v[3];
+    reduce_partials<3, 4u>(part_mass, nb, v);
+    if (flat_tid() == 0) {
+        st->mass_gas = (ph.rho_ref * (double)ncell(ph) + v[0]) * ph.V;
+        st->usq = v[1];
+        st->rho_min = -v[2];
+        if (!isfinite(v[0]) || !isfinite(v[1])) st->flags |= 2;
+        if (!(-v[2] > 0.0)) st->flags |= 4;
+    }
+    for (int c = 0; c < ncls; ++c) {
+        double m[1];
+        reduce_partials<1, 0u>(part_dust + (size_t)c * cls_stride, nb, m);
+        if (flat_tid() == 0) st->mass_p[c] = m[0] * ph.V;
     }
 }
 
 // ------------------------------------------------------------------------
 // launch wrappers
 // ------------------------------------------------------------------------
-Launch make_launch(int n, int cz) {
+Launch make_launch(int n) {
     Launch L;
     const int bx = n >= 64 ? 64 : 32;
     const int by = kBlock / bx;
+    const int gx = (n + bx - 1) / bx, gy = (n + by - 1) / by;
+    // about kTargetBlocks blocks: the partials of a reduction stay small enough
+    // for every block of the consuming kernel to total them redundantly
+    int nz = kTargetBlocks / (gx * gy);
+    nz = nz < 1 ? 1 : (nz > n ? n : nz);
+    const int cz = (n + nz - 1) / nz;
+    nz = (n + cz - 1) / cz;
     L.block = dim3(bx, by, 1);
-    L.grid = dim3((n + bx - 1) / bx, (n + by - 1) / by, (n + cz - 1) / cz);
+    L.grid = dim3(gx, gy, nz);
+    L.nblocks = L.grid.x * L.grid.y * L.grid.z;
+    L.cz = cz;
+    return L;
+}
+
+Launch make_tiled_launch(int n) {
+    Launch L{};
+    if (n < 128 || n % kTX != 0 || n % kTY != 0) return L;   // nblocks = 0: not available
+    const int gx = n / kTX, gy = n / kTY;
+    int nz = kTiledBlocks / (gx * gy);
+    nz = nz < 1 ? 1 : nz;
+    int cz = (n + nz - 1) / nz;
+    if (cz < 8) cz = 8;
+    nz = (n + cz - 1) / cz;
+    L.block = dim3(kTX, kTY, 1);
+    L.grid = dim3(gx, gy, nz);
     L.nblocks = L.grid.x * L.grid.y * L.grid.z;
     L.cz = cz;
     return L;
@@ -620,15 +855,17 @@ void Ops<T>::init_phi(const Launch& L, hipStream_t s, const Phys& ph, const T* r
     LAUNCH(k_init_phi<T>, L, s, ph, r, u, phi);
 }
 template <typename T>
-void Ops<T>::cfl(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, const T* r,
-                 const T* phi, double* partials, double dt_fixed, double cfl, double growth,
-                 double dt_prev, double dt_max) {
-    LAUNCH(k_cfl<T>, L, s, ph, st, r, phi, partials, dt_fixed, cfl, growth, dt_prev, dt_max);
+void Ops<T>::cfl(const Launch& L, hipStream_t s, const Phys& ph, const T* r, const T* phi,
+                 double* part) {
+    LAUNCH(k_cfl<T>, L, s, ph, r, phi, part);
 }
 template <typename T>
-void Ops<T>::predict(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                     const T* rn, const T* un, const T* phi, T* rs, T* aP, T* divu, T* pn) {
-    LAUNCH(k_predict<T>, L, s, ph, st, rn, un, phi, rs, aP, divu, pn);
+void Ops<T>::predict(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
+                     const double* part_cfl, double dt_fixed, double cfl, double growth,
+                     double dt_prev, double dt_max, const T* rn, const T* un, const T* phi, T* rs,
+                     T* aP, T* divu, T* pn) {
+    LAUNCH(k_predict<T>, L, s, ph, st, part_cfl, L.nblocks, dt_fixed, cfl, growth, dt_prev, dt_max,
+           rn, un, phi, rs, aP, divu, pn);
 }
 template <typename T>
 void Ops<T>::mom_source(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
@@ -649,21 +886,41 @@ void Ops<T>::hbya(const Launch& L, hipStream_t s, const Phys& ph, const T* uin, 
 template <typename T>
 void Ops<T>::corr_rhs(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, const T* rn,
                       const T* rk, const T* w, const T* hb, const T* p0, T* phiH, T* r, T* x,
-                      T* diag, double* partials, double* snap_b, double* snap_diag,
-                      double* snap_p0) {
-    LAUNCH(k_corr_rhs<T>, L, s, ph, st, rn, rk, w, hb, p0, phiH, r, x, diag, partials, snap_b,
-           snap_diag, snap_p0);
+                      T* diag, double* part_u, double* snap_b, double* snap_diag,
+                      double* snap_p0, double* b64, double* x64) {
+    LAUNCH(k_corr_rhs<T>, L, s, ph, st, rn, rk, w, hb, p0, phiH, r, x, diag, part_u, snap_b,
+           snap_diag, snap_p0, b64, x64);
 }
 template <typename T>
-void Ops<T>::pcg_spmv(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int k,
-                      const T* r, const T* diag, const T* w, const T* pold, T* pnew, T* q,
-                      double* partials) {
-    LAUNCH(k_pcg_spmv<T>, L, s, ph, st, k, r, diag, w, pold, pnew, q, partials);
+void Ops<T>::refine(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
+                    const double* x64, const T* d, double* x64n, const double* b64, const T* w,
+                    const T* diag, T* r32, double* part_u) {
+    LAUNCH(k_refine<T>, L, s, ph, st, x64, d, x64n, b64, w, diag, r32, part_u);
 }
 template <typename T>
-void Ops<T>::pcg_update(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int k, T* r,
-                        const T* q, const T* diag, T* x, const T* p, double* partials) {
-    LAUNCH(k_pcg_update<T>, L, s, ph, st, k, r, q, diag, x, p, partials);
+void Ops<T>::zero(hipStream_t s, T* a, size_t count) {
+    hipLaunchKernelGGL(k_zero<T>, lin_grid(count), dim3(kBlock), 0, s, a, count);
+}
+template <typename T>
+void Ops<T>::pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                      DevState* st, int k, const T* r, const T* diag, const T* w, const T* pold,
+                      T* pnew, T* q, const double* part_u, double* part_s, double tol2, int maxit) {
+    if (TL.nblocks) {
+        Phys pt = ph;
+        pt.cz = TL.cz;
+        LAUNCH(k_pcg_spmv_tiled<T>, TL, s, pt, st, k, r, diag, w, pold, pnew, q, part_u, L.nblocks,
+               part_s, tol2, maxit);
+    } else {
+        LAUNCH(k_pcg_spmv<T>, L, s, ph, st, k, r, diag, w, pold, pnew, q, part_u, part_s,
+               L.nblocks, tol2, maxit);
+    }
+}
+template <typename T>
+void Ops<T>::pcg_update(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                        const DevState* st, int k, T* r, const T* q, const T* diag, T* x,
+                        const T* p, const double* part_s, double* part_u) {
+    LAUNCH(k_pcg_update<T>, L, s, ph, st, k, r, q, diag, x, p, part_s, part_u,
+           TL.nblocks ? TL.nblocks : L.nblocks);
 }
 template <typename T>
 void Ops<T>::helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt, const T* w,
@@ -673,8 +930,8 @@ void Ops<T>::helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T*
 template <typename T>
 void Ops<T>::helm_start(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                         const T* psidt, const T* w, const T* b, const T* x, T* r, T* diag,
-                        double* partials) {
-    LAUNCH(k_helm_start<T>, L, s, ph, st, psidt, w, b, x, r, diag, partials);
+                        double* part_u) {
+    LAUNCH(k_helm_start<T>, L, s, ph, st, psidt, w, b, x, r, diag, part_u);
 }
 template <typename T>
 void Ops<T>::corr_flux(const Launch& L, hipStream_t s, const Phys& ph, const T* p0, const T* x,
@@ -682,13 +939,13 @@ void Ops<T>::corr_flux(const Launch& L, hipStream_t s, const Phys& ph, const T* 
     LAUNCH(k_corr_flux<T>, L, s, ph, p0, x, w, phiH, phik, pt, snap_x);
 }
 template <typename T>
-void Ops<T>::corr_update(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, bool last,
-                         const T* rn, const T* phik, const T* hb, const T* pt, const T* aP, T* rk,
-                         T* u, double* partials) {
+void Ops<T>::corr_update(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                         bool last, const T* rn, const T* phik, const T* hb, const T* pt,
+                         const T* aP, T* rk, T* u, double* part_mass) {
     if (last)
-        LAUNCH((k_corr_update<T, true>), L, s, ph, st, rn, phik, hb, pt, aP, rk, u, partials);
+        LAUNCH((k_corr_update<T, true>), L, s, ph, st, rn, phik, hb, pt, aP, rk, u, part_mass);
     else
-        LAUNCH((k_corr_update<T, false>), L, s, ph, st, rn, phik, hb, pt, aP, rk, u, partials);
+        LAUNCH((k_corr_update<T, false>), L, s, ph, st, rn, phik, hb, pt, aP, rk, u, part_mass);
 }
 template <typename T>
 void Ops<T>::dudt(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st, const T* un,
@@ -710,19 +967,28 @@ void Ops<T>::dust_faceflux(const Launch& L, hipStream_t s, const Phys& ph, const
     LAUNCH(k_dust_faceflux<T>, L, s, ph, Y, G);
 }
 template <typename T>
-void Ops<T>::dust_finish(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int cls,
-                         const T* rhoj, const T* F, T* rhoj1, double* partials) {
-    LAUNCH(k_dust_finish<T>, L, s, ph, st, cls, rhoj, F, rhoj1, partials);
+void Ops<T>::dust_finish(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                         const T* rhoj, const T* F, T* rhoj1, double* part) {
+    LAUNCH(k_dust_finish<T>, L, s, ph, st, rhoj, F, rhoj1, part);
 }
 template <typename T>
-void Ops<T>::stats_gas(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, const T* r,
-                       const T* u, double* partials) {
-    LAUNCH(k_stats_gas<T>, L, s, ph, st, r, u, partials);
+void Ops<T>::stats_gas(const Launch& L, hipStream_t s, const Phys& ph, const T* r, const T* u,
+                       double* part) {
+    LAUNCH(k_stats_gas<T>, L, s, ph, r, u, part);
 }
 template <typename T>
-void Ops<T>::sum_affine_sq(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
-                           const T* x, double a, double b, int slot, double* partials) {
-    LAUNCH(k_sum_affine_sq<T>, L, s, ph, st, x, a, b, slot, partials);
+void Ops<T>::sum_affine_sq(const Launch& L, hipStream_t s, const Phys& ph, const T* x, double a,
+                           double b, double* part) {
+    LAUNCH(k_sum_affine_sq<T>, L, s, ph, x, a, b, part);
+}
+
+void finalize_sums(hipStream_t s, const double* part, unsigned nb, int nv, double* dst) {
+    hipLaunchKernelGGL(k_finalize_sums, dim3(1), dim3(64, 4), 0, s, part, nb, nv, dst);
+}
+void step_finish(hipStream_t s, const Phys& ph, DevState* st, const double* part_mass,
+                 const double* part_dust, int ncls, unsigned nb, size_t cls_stride) {
+    hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(64, 4), 0, s, ph, st, part_mass, part_dust,
+                       ncls, nb, cls_stride);
 }
 
 template struct Ops<double>;

@@ -16,8 +16,28 @@ struct Launch {
     int cz;
 };
 
-// Blocks of 64x4 (n >= 64) or 32x8 threads over x-y; each thread walks cz cells along z.
-Launch make_launch(int n, int cz);
+constexpr int kTargetBlocks = 2048;
+constexpr int kTX = 64, kTY = 8;     // x-y tile of the z-marching kernels
+constexpr int kTiledBlocks = 1024;
+
+// Blocks of 64x4 (n >= 64) or 32x8 threads over x-y; each thread walks cz
+// consecutive cells along z, with cz chosen for about kTargetBlocks blocks.
+Launch make_launch(int n);
+
+// Launch of the LDS-tiled z-marching kernels (64 x 8 threads per block); nblocks
+// is 0 when n is not a multiple of the tile or below 128.
+Launch make_tiled_launch(int n);
+
+// Partial-sum slots in the workspace (columns of num_blocks doubles each).
+enum PartSlot {
+    PS_CFL = 0,    // 1 column: Courant maxima
+    PS_U = 1,      // 3 columns: r.z, r.r, b.b (CG second half / system set-up)
+    PS_S = 4,      // 1 column: p.q (CG first half)
+    PS_MASS = 5,   // 3 columns: sum r, sum |u|^2, max(-rho)
+    PS_STAT = 8,   // 4 columns: statistics
+    PS_DUST = 12,  // kMaxClasses columns: dust class masses
+    PS_COLUMNS = 12 + kMaxClasses
+};
 
 template <typename T>
 struct Ops {
@@ -26,11 +46,12 @@ struct Ops {
     static void pressure_out(hipStream_t s, const Phys& ph, const T* r, double* dst);
     static void init_phi(const Launch& L, hipStream_t s, const Phys& ph, const T* r, const T* u,
                          T* phi);
-    static void cfl(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, const T* r,
-                    const T* phi, double* partials, double dt_fixed, double cfl, double growth,
-                    double dt_prev, double dt_max);
-    static void predict(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                        const T* rn, const T* un, const T* phi, T* rs, T* aP, T* divu, T* pn);
+    static void cfl(const Launch& L, hipStream_t s, const Phys& ph, const T* r, const T* phi,
+                    double* part);
+    static void predict(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
+                        const double* part_cfl, double dt_fixed, double cfl, double growth,
+                        double dt_prev, double dt_max, const T* rn, const T* un, const T* phi,
+                        T* rs, T* aP, T* divu, T* pn);
     static void mom_source(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                            const T* rn, const T* un, const T* divu, T* src);
     static void mom_sweep(const Launch& L, hipStream_t s, const Phys& ph, const T* uin, T* uout,
@@ -39,23 +60,30 @@ struct Ops {
                      const T* phi, const T* aP, const T* src, const T* rk, T* w, T* p0);
     static void corr_rhs(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                          const T* rn, const T* rk, const T* w, const T* hb, const T* p0, T* phiH,
-                         T* r, T* x, T* diag, double* partials, double* snap_b,
-                         double* snap_diag, double* snap_p0);
-    static void pcg_spmv(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int k,
-                         const T* r, const T* diag, const T* w, const T* pold, T* pnew, T* q,
-                         double* partials);
-    static void pcg_update(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int k,
-                           T* r, const T* q, const T* diag, T* x, const T* p, double* partials);
+                         T* r, T* x, T* diag, double* part_u, double* snap_b, double* snap_diag,
+                         double* snap_p0, double* b64, double* x64);
+    static void refine(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
+                       const double* x64, const T* d, double* x64n, const double* b64,
+                       const T* w, const T* diag, T* r32, double* part_u);
+    static void zero(hipStream_t s, T* a, size_t count);
+    // TL: tiled launch (used when TL.nblocks > 0)
+    static void pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                         DevState* st, int k, const T* r, const T* diag, const T* w,
+                         const T* pold, T* pnew, T* q, const double* part_u, double* part_s,
+                         double tol2, int maxit);
+    static void pcg_update(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                           const DevState* st, int k, T* r, const T* q, const T* diag, T* x,
+                           const T* p, const double* part_s, double* part_u);
     static void helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt,
                            const T* w, const T* x, T* y);
     static void helm_start(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                            const T* psidt, const T* w, const T* b, const T* x, T* r, T* diag,
-                           double* partials);
+                           double* part_u);
     static void corr_flux(const Launch& L, hipStream_t s, const Phys& ph, const T* p0, const T* x,
                           const T* w, const T* phiH, T* phik, T* pt, double* snap_x);
-    static void corr_update(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
+    static void corr_update(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                             bool last, const T* rn, const T* phik, const T* hb, const T* pt,
-                            const T* aP, T* rk, T* u, double* partials);
+                            const T* aP, T* rk, T* u, double* part_mass);
     static void dudt(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                      const T* un, const T* u1, T* acc);
     static void dust_flux(const Launch& L, hipStream_t s, const Phys& ph, double tau,
@@ -64,12 +92,18 @@ struct Ops {
     static void dust_sweep(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                            const T* Yin, T* Yout, const T* G, const T* rhoj, const T* r1);
     static void dust_faceflux(const Launch& L, hipStream_t s, const Phys& ph, const T* Y, T* G);
-    static void dust_finish(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int cls,
-                            const T* rhoj, const T* F, T* rhoj1, double* partials);
-    static void stats_gas(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
-                          const T* r, const T* u, double* partials);
-    static void sum_affine_sq(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
-                              const T* x, double a, double b, int slot, double* partials);
+    static void dust_finish(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                            const T* rhoj, const T* F, T* rhoj1, double* part);
+    static void stats_gas(const Launch& L, hipStream_t s, const Phys& ph, const T* r, const T* u,
+                          double* part);
+    static void sum_affine_sq(const Launch& L, hipStream_t s, const Phys& ph, const T* x,
+                              double a, double b, double* part);
 };
+
+// One-block totals of nv partial columns into dst (device).
+void finalize_sums(hipStream_t s, const double* part, unsigned nb, int nv, double* dst);
+// One-block end-of-step mass budget and flags.
+void step_finish(hipStream_t s, const Phys& ph, DevState* st, const double* part_mass,
+                 const double* part_dust, int ncls, unsigned nb, size_t cls_stride);
 
 }  // namespace pisoc

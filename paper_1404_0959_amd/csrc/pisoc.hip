@@ -11,9 +11,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/pisoc.h"
 #include "device.hpp"
@@ -35,11 +37,63 @@ struct Layout {
     size_t u3[3], phin, phik, src, hbya, phiH, acc, G;
     size_t rhop, rhop1;
     size_t snap;   // 4 FP64 fields when capturing
+    size_t b64, x64a, x64b;  // FP64 refinement fields (FP32 storage only)
     size_t total;
     unsigned max_blocks;
 };
 
-int pick_cz(int n) { return n >= 128 ? 8 : (n >= 64 ? 4 : 1); }
+
+// Kernel classes for the optional per-launch event timing.
+enum KCls {
+    KC_CFL, KC_PREDICT, KC_MOM_SOURCE, KC_MOM_SWEEP, KC_HBYA, KC_CORR_RHS, KC_PCG_SPMV,
+    KC_PCG_UPDATE, KC_CORR_FLUX, KC_CORR_UPDATE, KC_DUDT, KC_DUST_FLUX, KC_DUST_SWEEP,
+    KC_DUST_FACEFLUX, KC_DUST_FINISH, KC_REFINE, KC_COUNT
+};
+const char* const kKernelName[KC_COUNT] = {
+    "k_cfl", "k_predict", "k_mom_source", "k_mom_sweep", "k_hbya", "k_corr_rhs",
+    "k_pcg_spmv", "k_pcg_update", "k_corr_flux", "k_corr_update", "k_dudt", "k_dust_flux",
+    "k_dust_sweep", "k_dust_faceflux", "k_dust_finish", "k_refine"};
+
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec { int cls; size_t ea, eb; double bytes; int k; };
+    std::vector<Rec> pending;
+    pisoc_kernel_stat stat[KC_COUNT];
+
+    size_t take() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return (size_t)-1;
+            pool.push_back(e);
+        }
+        return used++;
+    }
+    void reset() {
+        std::memset(stat, 0, sizeof(stat));
+        for (int i = 0; i < KC_COUNT; ++i)
+            std::snprintf(stat[i].name, sizeof(stat[i].name), "%s", kKernelName[i]);
+        pending.clear();
+        used = 0;
+    }
+    // Attribute completed launches; CG launches with k >= it_stop returned at once.
+    void resolve(int it_stop) {
+        for (const Rec& r : pending) {
+            if (r.k >= 0 && r.k >= it_stop) continue;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pool[r.ea], pool[r.eb]) != hipSuccess) continue;
+            stat[r.cls].launches += 1;
+            stat[r.cls].ms += ms;
+            stat[r.cls].bytes += r.bytes;
+        }
+        pending.clear();
+        used = 0;
+    }
+    ~Prof() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
 
 bool valid_params(const pisoc_params* p, std::string* why) {
     auto fail = [&](const char* m) { if (why) *why = m; return false; };
@@ -56,7 +110,9 @@ bool valid_params(const pisoc_params* p, std::string* why) {
         if (!(p->tau_p[c] >= 0.0)) return fail("tau_p must be >= 0");
     if (p->precision != PISOC_FP64 && p->precision != PISOC_FP32_REFINED)
         return fail("unknown precision");
-    if (p->precision == PISOC_FP32_REFINED) return fail("FP32_REFINED is not built yet");
+    if (p->precision == PISOC_FP32_REFINED &&
+        (!(p->inner_tol > 0.0) || !(p->inner_tol < 1.0) || p->max_refine < 1))
+        return fail("FP32_REFINED needs 0 < inner_tol < 1 and max_refine >= 1");
     if (p->guess != PISOC_GUESS_ZERO) return fail("learned guess is not built yet");
     return true;
 }
@@ -65,12 +121,12 @@ Layout make_layout(const pisoc_params* p) {
     Layout L{};
     const size_t N = (size_t)p->n * p->n * p->n;
     const size_t es = p->precision == PISOC_FP64 ? sizeof(double) : sizeof(float);
-    const Launch lc = make_launch(p->n, pick_cz(p->n));
-    L.max_blocks = lc.nblocks;
+    const Launch lc = make_launch(p->n);
+    L.max_blocks = std::max(lc.nblocks, make_tiled_launch(p->n).nblocks);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     L.state = take(sizeof(DevState));
-    L.partials = take(sizeof(double) * kMaxRed * (size_t)L.max_blocks);
+    L.partials = take(sizeof(double) * PS_COLUMNS * (size_t)L.max_blocks);
     size_t* one[] = {&L.rn, &L.rk, &L.aP, &L.divu, &L.pn, &L.w, &L.p0, &L.r, &L.x, &L.diag,
                      &L.pp0, &L.pp1, &L.q, &L.Y0, &L.Y1};
     for (size_t* o : one) *o = take(es * N);
@@ -80,6 +136,11 @@ Layout make_layout(const pisoc_params* p) {
     L.rhop = take(es * N * (size_t)std::max(p->n_classes, 1));
     L.rhop1 = take(es * N * (size_t)std::max(p->n_classes, 1));
     L.snap = p->capture ? take(4 * sizeof(double) * N) : 0;
+    if (p->precision == PISOC_FP32_REFINED) {
+        L.b64 = take(sizeof(double) * N);
+        L.x64a = take(sizeof(double) * N);
+        L.x64b = take(sizeof(double) * N);
+    }
     L.total = off;
     return L;
 }
@@ -93,6 +154,7 @@ struct pisoc_ctx {
     Layout lay;
     Phys ph;
     Launch L;
+    Launch TL;      // tiled z-marching launch (nblocks = 0 when not available)
     DevState* st;
     DevState* hst;  // pinned host copy
     double* partials;
@@ -102,10 +164,15 @@ struct pisoc_ctx {
     double t, dt_prev;
     int64_t steps;
     int last_iters[PISOC_MAX_CORR];
+    int last_first[PISOC_MAX_CORR];  // FP32 mode: iterations of the first inner solve
+    size_t es;      // bytes per field element (8 or 4)
+    Prof prof;
     std::string err;
 
     template <typename T> T* f(size_t off) const { return reinterpret_cast<T*>(ws + off); }
     size_t N() const { return (size_t)prm.n * prm.n * prm.n; }
+    // partial-sum column `slot` (num_blocks doubles per column)
+    double* part(int slot) const { return partials + (size_t)slot * lay.max_blocks; }
 };
 
 namespace {
@@ -121,6 +188,25 @@ pisoc_status hip_fail(pisoc_ctx* ctx, hipError_t e, const char* where) {
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
     } while (0)
 
+// Run `launch` (one kernel launch), bracketed by events when profiling.
+template <class F>
+void timed(pisoc_ctx* ctx, int cls, double words, int k, F&& launch) {
+    Prof& P = ctx->prof;
+    if (!P.on) {
+        launch();
+        return;
+    }
+    const size_t a = P.take(), b = P.take();
+    if (a == (size_t)-1 || b == (size_t)-1) {
+        launch();
+        return;
+    }
+    (void)hipEventRecord(P.pool[a], ctx->stream);
+    launch();
+    (void)hipEventRecord(P.pool[b], ctx->stream);
+    P.pending.push_back({cls, a, b, words * (double)ctx->es * (double)ctx->N(), k});
+}
+
 pisoc_status sync_state(pisoc_ctx* ctx) {
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipMemcpyAsync(ctx->hst, ctx->st, sizeof(DevState), hipMemcpyDeviceToHost,
@@ -132,7 +218,7 @@ pisoc_status sync_state(pisoc_ctx* ctx) {
 Phys make_phys(const pisoc_params* p, double rho_ref) {
     Phys ph{};
     ph.n = p->n;
-    ph.cz = pick_cz(p->n);
+    ph.cz = make_launch(p->n).cz;
     ph.h = kTwoPi / p->n;
     ph.inv_h = 1.0 / ph.h;
     ph.inv_h2 = 1.0 / (ph.h * ph.h);
@@ -147,34 +233,108 @@ Phys make_phys(const pisoc_params* p, double rho_ref) {
     return ph;
 }
 
-// CG on the system already set up by corr_rhs / helm_start.  Launches batches
-// of (spmv, update) pairs; later launches of a converged solve return at once.
+// CG on the system already set up by corr_rhs / helm_start (which left the
+// partials r0.z0, r0.r0, b.b).  Launches the first half of iteration 0, then
+// batches of (second half k, first half k+1) pairs; the first half of k+1
+// tests convergence, so a batch always ends on a test.  Launches after the
+// stop return at once.
 template <typename T>
 pisoc_status run_pcg(pisoc_ctx* ctx, T* r, T* x, T* diag, T* w, T* pp0, T* pp1, T* q,
-                     int predicted, int32_t* iters, double* relres, bool* converged) {
+                     double tol, int predicted, int32_t* iters, double* relres, bool* converged) {
     using O = Ops<T>;
     const int maxit = ctx->prm.p_maxit;
     T* pp[2] = {pp0, pp1};
-    int k = 0;
+    double* pu = ctx->part(PS_U);
+    double* ps = ctx->part(PS_S);
+    auto spmv = [&](int k) {
+        timed(ctx, KC_PCG_SPMV, k == 0 ? 5.0 : 6.0, k, [&] {
+            O::pcg_spmv(ctx->L, ctx->TL, ctx->stream, ctx->ph, ctx->st, k, r, diag, w,
+                        pp[(k + 1) & 1], pp[k & 1], q, pu, ps, tol * tol, maxit);
+        });
+    };
+    auto update = [&](int k) {
+        timed(ctx, KC_PCG_UPDATE, 7.0, k, [&] {
+            O::pcg_update(ctx->L, ctx->TL, ctx->stream, ctx->ph, ctx->st, k, r, q, diag, x, pp[k & 1],
+                          ps, pu);
+        });
+    };
+    spmv(0);
+    int k = 0;  // first halves launched: 0..k
     int batch = std::max(1, predicted);
     for (;;) {
         const int kend = std::min(k + batch, maxit);
         for (; k < kend; ++k) {
-            O::pcg_spmv(ctx->L, ctx->stream, ctx->ph, ctx->st, k, r, diag, w, pp[(k + 1) & 1],
-                        pp[k & 1], q, ctx->partials);
-            O::pcg_update(ctx->L, ctx->stream, ctx->ph, ctx->st, k, r, q, diag, x, pp[k & 1],
-                          ctx->partials);
+            update(k);
+            spmv(k + 1);
         }
         pisoc_status s = sync_state(ctx);
         if (s != PISOC_OK) return s;
+        if (ctx->prof.on) ctx->prof.resolve(ctx->hst->pcg.it_stop);
         if (ctx->hst->flags & PISOC_FLAG_BAD_DT) break;
-        if (ctx->hst->pcg.it_stop <= k || k >= maxit) break;
-        batch = 4;
+        if (ctx->hst->pcg.it_stop != kIterInf || k >= maxit) break;
+        batch = 2;
     }
     const PcgState& g = ctx->hst->pcg;
     *iters = g.iters;
     *relres = g.bb > 0.0 ? std::sqrt(g.rr / g.bb) : 0.0;
     *converged = g.converged != 0;
+    return PISOC_OK;
+}
+
+// FP32 storage: mixed-precision iterative refinement of M p' = b.  Inner
+// solves are FP32 CG to a relative tolerance tau; after each, k_refine adds the
+// correction to the FP64 accumulator and evaluates the true residual in FP64;
+// the loop ends when ||r64|| <= p_tol ||b64||.
+pisoc_status refine_solve(pisoc_ctx* ctx, float* r, float* x, float* diag, float* w, float* pp0,
+                          float* pp1, float* q, int corr, int32_t* iters, double* relres,
+                          bool* converged, int32_t* rounds) {
+    const pisoc_params& p = ctx->prm;
+    double* b64 = ctx->f<double>(ctx->lay.b64);
+    double* xa = ctx->f<double>(ctx->lay.x64a);
+    double* xb = ctx->f<double>(ctx->lay.x64b);
+    const size_t N = ctx->N();
+    int32_t it = 0, total = 0;
+    double rel = 0.0;
+    bool conv = false;
+    const int pred0 = ctx->last_first[corr] > 0 ? ctx->last_first[corr] : 8;
+    const double tau0 = std::min(0.5, std::max(0.5 * p.p_tol, p.inner_tol));
+    pisoc_status st = run_pcg<float>(ctx, r, x, diag, w, pp0, pp1, q, tau0, pred0, &it, &rel,
+                                     &conv);
+    if (st != PISOC_OK) return st;
+    ctx->last_first[corr] = it;
+    total += it;
+    const double bb = ctx->hst->pcg.bb;
+    double rr = bb;
+    int nround = 0;
+    if (bb > 0.0) {
+        for (;;) {
+            timed(ctx, KC_REFINE, 10, -1, [&] {
+                Ops<float>::refine(ctx->L, ctx->stream, ctx->ph, ctx->st, xa, x, xb, b64, w, diag, r,
+                                   ctx->part(PS_U));
+            });
+            std::swap(xa, xb);
+            // column 1 (||r64||^2) of the 3-column block written with L.nblocks blocks
+            finalize_sums(ctx->stream, ctx->part(PS_U) + ctx->L.nblocks, ctx->L.nblocks, 1,
+                          ctx->st->red);
+            if ((st = sync_state(ctx)) != PISOC_OK) return st;
+            if (ctx->prof.on) ctx->prof.resolve(kIterInf);
+            rr = ctx->hst->red[0];
+            ++nround;
+            if (rr <= p.p_tol * p.p_tol * bb || nround >= p.max_refine || !std::isfinite(rr)) break;
+            double tau = 0.5 * p.p_tol * std::sqrt(bb / rr);
+            tau = std::min(0.5, std::max(tau, p.inner_tol));
+            Ops<float>::zero(ctx->stream, x, N);
+            st = run_pcg<float>(ctx, r, x, diag, w, pp0, pp1, q, tau, 2, &it, &rel, &conv);
+            if (st != PISOC_OK) return st;
+            total += it;
+        }
+    }
+    // the corrector uses the FP32 copy of the FP64 solution
+    Ops<float>::cast_in(ctx->stream, xa, x, N, 0.0);
+    *iters = total;
+    *relres = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+    *converged = rr <= p.p_tol * p.p_tol * bb;
+    *rounds = nround;
     return PISOC_OK;
 }
 
@@ -187,7 +347,6 @@ pisoc_status one_step(pisoc_ctx* ctx, pisoc_step_info* info) {
     hipStream_t s = ctx->stream;
     const size_t N = ctx->N();
     DevState* st = ctx->st;
-    double* part = ctx->partials;
     auto F = [&](size_t off) { return ctx->f<T>(off); };
     const Layout& Y = ctx->lay;
 
@@ -202,35 +361,48 @@ pisoc_status one_step(pisoc_ctx* ctx, pisoc_step_info* info) {
     T *w = F(Y.w), *p0 = F(Y.p0), *phiH = F(Y.phiH), *r = F(Y.r), *x = F(Y.x), *dg = F(Y.diag);
     T *pp0 = F(Y.pp0), *pp1 = F(Y.pp1), *q = F(Y.q);
     double* snap = p.capture ? reinterpret_cast<double*>(ctx->ws + Y.snap) : nullptr;
+    const bool f32 = sizeof(T) == sizeof(float);
 
     pisoc_step_info rec{};
     int flags = 0;
     pisoc_status worst = PISOC_OK;
 
     HIP_TRY(ctx, hipMemsetAsync(&st->flags, 0, sizeof(int32_t), s));
-    O::cfl(L, s, ph, st, rn, phin, part, p.dt_fixed, p.cfl, p.dt_growth, ctx->dt_prev, p.dt_max);
-    O::predict(L, s, ph, st, rn, un, phin, rk, aP, divu, pn);
-    O::mom_source(L, s, ph, st, rn, un, divu, src);
+    timed(ctx, KC_CFL, 4, -1, [&] { O::cfl(L, s, ph, rn, phin, ctx->part(PS_CFL)); });
+    timed(ctx, KC_PREDICT, 11, -1, [&] {
+        O::predict(L, s, ph, st, ctx->part(PS_CFL), p.dt_fixed, p.cfl, p.dt_growth, ctx->dt_prev,
+                   p.dt_max, rn, un, phin, rk, aP, divu, pn);
+    });
+    timed(ctx, KC_MOM_SOURCE, 8, -1, [&] { O::mom_source(L, s, ph, st, rn, un, divu, src); });
     T* uin = un;
     for (int i = 0; i < p.n_mom_sweeps; ++i) {
         T* uout = (i & 1) ? ub : ua;
-        O::mom_sweep(L, s, ph, uin, uout, phin, aP, src, pn);
+        timed(ctx, KC_MOM_SWEEP, 14, -1, [&] { O::mom_sweep(L, s, ph, uin, uout, phin, aP, src, pn); });
         uin = uout;
     }
     T* ucur = uin;
     const int ucur_slot = (ucur == ua) ? 1 : 2;
 
     for (int corr = 0; corr < p.n_corr; ++corr) {
-        O::hbya(L, s, ph, ucur, hb, phin, aP, src, rk, w, p0);
+        timed(ctx, KC_HBYA, 16, -1, [&] { O::hbya(L, s, ph, ucur, hb, phin, aP, src, rk, w, p0); });
         const bool cap = snap && corr == 0;
-        O::corr_rhs(L, s, ph, st, rn, rk, w, hb, p0, phiH, r, x, dg, part,
-                    cap ? snap : nullptr, cap ? snap + N : nullptr, cap ? snap + 2 * N : nullptr);
-        int32_t it = 0;
+        timed(ctx, KC_CORR_RHS, f32 ? 17 : 13, -1, [&] {
+            O::corr_rhs(L, s, ph, st, rn, rk, w, hb, p0, phiH, r, x, dg, ctx->part(PS_U),
+                        cap ? snap : nullptr, cap ? snap + N : nullptr,
+                        cap ? snap + 2 * N : nullptr, f32 ? ctx->f<double>(Y.b64) : nullptr,
+                        f32 ? ctx->f<double>(Y.x64a) : nullptr);
+        });
+        int32_t it = 0, rounds = 0;
         double rel = 0.0;
         bool conv = false;
-        const int pred = ctx->last_iters[corr] > 0 ? ctx->last_iters[corr] + 1 : 8;
-        pisoc_status ps = run_pcg<T>(ctx, r, x, dg, w, pp0, pp1, q, pred, &it, &rel, &conv);
+        const int pred = ctx->last_iters[corr] > 0 ? ctx->last_iters[corr] : 8;
+        pisoc_status ps;
+        if constexpr (sizeof(T) == sizeof(float))
+            ps = refine_solve(ctx, r, x, dg, w, pp0, pp1, q, corr, &it, &rel, &conv, &rounds);
+        else
+            ps = run_pcg<T>(ctx, r, x, dg, w, pp0, pp1, q, p.p_tol, pred, &it, &rel, &conv);
         if (ps != PISOC_OK) return ps;
+        rec.refinements[corr] = rounds;
         if (ctx->hst->flags & PISOC_FLAG_BAD_DT) {
             ctx->err = "time step undefined or non-positive (zero velocity needs dt_fixed or dt_max)";
             return PISOC_ERR_INVALID;
@@ -242,8 +414,13 @@ pisoc_status one_step(pisoc_ctx* ctx, pisoc_step_info* info) {
             flags |= PISOC_FLAG_PCG_MAXIT;
             worst = PISOC_WARN_NOT_CONVERGED;
         }
-        O::corr_flux(L, s, ph, p0, x, w, phiH, phik, q, cap ? snap + 3 * N : nullptr);
-        O::corr_update(L, s, ph, st, corr == p.n_corr - 1, rn, phik, hb, q, aP, rk, ucur, part);
+        timed(ctx, KC_CORR_FLUX, 10, -1, [&] {
+            O::corr_flux(L, s, ph, p0, x, w, phiH, phik, q, cap ? snap + 3 * N : nullptr);
+        });
+        timed(ctx, KC_CORR_UPDATE, 13, -1, [&] {
+            O::corr_update(L, s, ph, st, corr == p.n_corr - 1, rn, phik, hb, q, aP, rk, ucur,
+                           ctx->part(PS_MASS));
+        });
     }
 
     if (p.n_classes > 0) {
@@ -253,22 +430,29 @@ pisoc_status one_step(pisoc_ctx* ctx, pisoc_step_info* info) {
         T* Yb = F(Y.Y1);
         T* rj = F(ctx->rhop);
         T* rj1 = F(ctx->rhop1);
-        O::dudt(L, s, ph, st, un, ucur, acc);
+        timed(ctx, KC_DUDT, 9, -1, [&] { O::dudt(L, s, ph, st, un, ucur, acc); });
         for (int c = 0; c < p.n_classes; ++c) {
-            O::dust_flux(L, s, ph, p.tau_p[c], phik, rk, acc, G, rj + c * N, rn, Ya);
+            timed(ctx, KC_DUST_FLUX, 13, -1, [&] {
+                O::dust_flux(L, s, ph, p.tau_p[c], phik, rk, acc, G, rj + c * N, rn, Ya);
+            });
             T* yin = Ya;
             T* yout = Yb;
             for (int i = 0; i < p.n_dust_sweeps; ++i) {
-                O::dust_sweep(L, s, ph, st, yin, yout, G, rj + c * N, rk);
+                timed(ctx, KC_DUST_SWEEP, 7, -1,
+                      [&] { O::dust_sweep(L, s, ph, st, yin, yout, G, rj + c * N, rk); });
                 std::swap(yin, yout);
             }
-            O::dust_faceflux(L, s, ph, yin, G);
-            O::dust_finish(L, s, ph, st, c, rj + c * N, G, rj1 + c * N, part);
+            timed(ctx, KC_DUST_FACEFLUX, 7, -1, [&] { O::dust_faceflux(L, s, ph, yin, G); });
+            timed(ctx, KC_DUST_FINISH, 5, -1,
+                  [&] { O::dust_finish(L, s, ph, st, rj + c * N, G, rj1 + c * N, ctx->part(PS_DUST + c)); });
         }
     }
+    step_finish(s, ph, st, ctx->part(PS_MASS), ctx->part(PS_DUST), p.n_classes, L.nblocks,
+                Y.max_blocks);
 
     pisoc_status ss = sync_state(ctx);
     if (ss != PISOC_OK) return ss;
+    if (ctx->prof.on) ctx->prof.resolve(kIterInf);
     const DevState& h = *ctx->hst;
     flags |= h.flags;
     if (h.flags & PISOC_FLAG_BAD_DT) {
@@ -348,7 +532,10 @@ pisoc_status pisoc_init(const pisoc_params* prm, void* d_workspace, size_t ws_by
     ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
     ctx->ws = reinterpret_cast<char*>(d_workspace);
     ctx->lay = lay;
-    ctx->L = make_launch(prm->n, pick_cz(prm->n));
+    ctx->L = make_launch(prm->n);
+    ctx->TL = make_tiled_launch(prm->n);
+    // PISOC_UNTILED=1 selects the untiled CG kernel (kernel-comparison tests)
+    if (const char* e = std::getenv("PISOC_UNTILED"); e && e[0] == '1') ctx->TL = Launch{};
     ctx->st = reinterpret_cast<DevState*>(ctx->ws + lay.state);
     ctx->partials = reinterpret_cast<double*>(ctx->ws + lay.partials);
     ctx->u_idx[0] = 0;
@@ -363,6 +550,8 @@ pisoc_status pisoc_init(const pisoc_params* prm, void* d_workspace, size_t ws_by
     ctx->t = 0.0;
     ctx->dt_prev = __builtin_inf();
     ctx->steps = 0;
+    ctx->es = prm->precision == PISOC_FP64 ? sizeof(double) : sizeof(float);
+    ctx->prof.reset();
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&ctx->hst), sizeof(DevState),
                                  hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -379,7 +568,8 @@ pisoc_status pisoc_init(const pisoc_params* prm, void* d_workspace, size_t ws_by
 
     // reference density = mean of the initial density (FP64 reduction of the input)
     Phys ph0 = make_phys(prm, 1.0);
-    Ops<double>::sum_affine_sq(ctx->L, s, ph0, ctx->st, d_rho, 0.0, 0.0, 0, ctx->partials);
+    Ops<double>::sum_affine_sq(ctx->L, s, ph0, d_rho, 0.0, 0.0, ctx->part(PS_STAT));
+    finalize_sums(s, ctx->part(PS_STAT), ctx->L.nblocks, 2, ctx->st->red);
     if (sync_state(ctx) != PISOC_OK) return fail(PISOC_ERR_HIP);
     const double rho_ref = ctx->hst->red[1] / (double)N;
     if (!(rho_ref > 0.0) || !std::isfinite(rho_ref)) return fail(PISOC_ERR_INVALID);
@@ -482,12 +672,14 @@ pisoc_status pisoc_get_stats(pisoc_ctx* ctx, pisoc_stats* out) {
     const bool f64 = ctx->prm.precision == PISOC_FP64;
     auto gas = [&](auto tag) {
         using T = decltype(tag);
-        Ops<T>::stats_gas(ctx->L, s, ph, ctx->st, ctx->f<T>(ctx->rn),
-                          ctx->f<T>(ctx->lay.u3[ctx->u_idx[0]]), ctx->partials);
+        Ops<T>::stats_gas(ctx->L, s, ph, ctx->f<T>(ctx->rn), ctx->f<T>(ctx->lay.u3[ctx->u_idx[0]]),
+                          ctx->part(PS_STAT));
+        finalize_sums(s, ctx->part(PS_STAT), ctx->L.nblocks, 4, ctx->st->red);
     };
     auto affine = [&](auto tag, size_t off, double a, double b) {
         using T = decltype(tag);
-        Ops<T>::sum_affine_sq(ctx->L, s, ph, ctx->st, ctx->f<T>(off), a, b, 4, ctx->partials);
+        Ops<T>::sum_affine_sq(ctx->L, s, ph, ctx->f<T>(off), a, b, ctx->part(PS_STAT));
+        finalize_sums(s, ctx->part(PS_STAT), ctx->L.nblocks, 2, ctx->st->red + 4);
     };
     if (f64) gas(double{}); else gas(float{});
     pisoc_status st = sync_state(ctx);
@@ -521,6 +713,22 @@ pisoc_status pisoc_get_stats(pisoc_ctx* ctx, pisoc_stats* out) {
     return PISOC_OK;
 }
 
+pisoc_status pisoc_profile(pisoc_ctx* ctx, int32_t enable) {
+    if (!ctx) return PISOC_ERR_INVALID;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return PISOC_ERR_HIP;
+    ctx->prof.reset();
+    ctx->prof.on = enable != 0;
+    return PISOC_OK;
+}
+
+int32_t pisoc_profile_read(const pisoc_ctx* ctx, pisoc_kernel_stat* out, int32_t max) {
+    if (!ctx || !out) return 0;
+    int32_t n = 0;
+    for (int i = 0; i < KC_COUNT && n < max; ++i)
+        if (ctx->prof.stat[i].launches > 0) out[n++] = ctx->prof.stat[i];
+    return n;
+}
+
 double pisoc_time(const pisoc_ctx* ctx) { return ctx ? ctx->t : 0.0; }
 int64_t pisoc_steps_done(const pisoc_ctx* ctx) { return ctx ? ctx->steps : 0; }
 
@@ -536,12 +744,12 @@ const char* pisoc_last_error(const pisoc_ctx* ctx) { return ctx ? ctx->err.c_str
 static Layout helm_layout(int32_t n) {
     Layout L{};
     const size_t N = (size_t)n * n * n;
-    const Launch lc = make_launch(n, pick_cz(n));
-    L.max_blocks = lc.nblocks;
+    const Launch lc = make_launch(n);
+    L.max_blocks = std::max(lc.nblocks, make_tiled_launch(n).nblocks);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     L.state = take(sizeof(DevState));
-    L.partials = take(sizeof(double) * kMaxRed * (size_t)L.max_blocks);
+    L.partials = take(sizeof(double) * PS_COLUMNS * (size_t)L.max_blocks);
     L.r = take(8 * N);
     L.diag = take(8 * N);
     L.pp0 = take(8 * N);
@@ -565,7 +773,7 @@ pisoc_status pisoc_helm_apply(int32_t n, const double* d_psidt, const double* d_
     p.gamma = 1.4;
     p.C = 1.0;
     Phys ph = make_phys(&p, 1.0);
-    Launch L = make_launch(n, ph.cz);
+    Launch L = make_launch(n);
     Ops<double>::helm_apply(L, reinterpret_cast<hipStream_t>(hip_stream), ph, d_psidt, d_w, d_x, d_y);
     return hipGetLastError() == hipSuccess ? PISOC_OK : PISOC_ERR_HIP;
 }
@@ -590,7 +798,8 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
     ctx.ws = reinterpret_cast<char*>(d_workspace);
     ctx.lay = lay;
     ctx.ph = make_phys(&ctx.prm, 1.0);
-    ctx.L = make_launch(n, ctx.ph.cz);
+    ctx.L = make_launch(n);
+    ctx.TL = make_tiled_launch(n);
     ctx.st = reinterpret_cast<DevState*>(ctx.ws + lay.state);
     ctx.partials = reinterpret_cast<double*>(ctx.ws + lay.partials);
     if (hipHostMalloc(reinterpret_cast<void**>(&ctx.hst), sizeof(DevState), hipHostMallocDefault) !=
@@ -609,12 +818,13 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
         double* r = ctx.f<double>(lay.r);
         double* dg = ctx.f<double>(lay.diag);
         Ops<double>::helm_start(ctx.L, ctx.stream, ctx.ph, ctx.st, d_psidt, d_w, d_b, d_x, r, dg,
-                                ctx.partials);
+                                ctx.part(PS_U));
         int32_t it = 0;
         double rel = 0.0;
         bool conv = false;
         st = run_pcg<double>(&ctx, r, d_x, dg, const_cast<double*>(d_w), ctx.f<double>(lay.pp0),
-                             ctx.f<double>(lay.pp1), ctx.f<double>(lay.q), 16, &it, &rel, &conv);
+                             ctx.f<double>(lay.pp1), ctx.f<double>(lay.q), tol, 16, &it, &rel,
+                             &conv);
         if (st == PISOC_OK) {
             if (iters) *iters = it;
             if (relres) *relres = rel;

@@ -83,18 +83,24 @@ def solenoidal_velocity(n: int, seed: int, k0: float = 4.0, u_prime: float = 1.0
 
 
 def spectral_dissipation(u, nu: float) -> float:
-    """eps0 = 2 nu <S:S> of a periodic field, with exact (Fourier) derivatives."""
+    """eps0 = 2 nu <S:S> of a periodic field with exact (Fourier) derivatives,
+    summed in spectral space (Parseval) over the rfftn half space."""
     n = u[0].shape[0]
-    kf = np.fft.fftfreq(n, d=1.0 / n)
-    kvec = [kf[None, None, :], kf[None, :, None], kf[:, None, None]]   # x, y, z
-    uh = [np.fft.fftn(c) for c in u]
-    grad = [[np.real(np.fft.ifftn(1j * kvec[b] * uh[a])) for b in range(3)] for a in range(3)]
+    kx, ky, kz = _wavenumbers(n)
+    kvec = (kx, ky, kz)
+    uh = [np.fft.rfftn(c, axes=(0, 1, 2)) for c in u]
+    # half-space weights: interior kx planes stand for +kx and -kx
+    wgt = np.full(n // 2 + 1, 2.0)
+    wgt[0] = 1.0
+    if n % 2 == 0:
+        wgt[-1] = 1.0
+    wgt = wgt[None, None, :]
     ss = 0.0
     for a in range(3):
         for b in range(3):
-            s_ab = 0.5 * (grad[a][b] + grad[b][a])
-            ss += float(np.mean(s_ab * s_ab))
-    return 2.0 * nu * ss
+            s_ab = 0.5j * (kvec[b] * uh[a] + kvec[a] * uh[b])
+            ss += float(np.sum(wgt * np.abs(s_ab) ** 2))
+    return 2.0 * nu * ss / float(n) ** 6
 
 
 @dataclasses.dataclass

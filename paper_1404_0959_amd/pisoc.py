@@ -29,7 +29,10 @@ EXPORTED = [
     "pisoc_workspace_bytes", "pisoc_init", "pisoc_step", "pisoc_fields", "pisoc_get_stats",
     "pisoc_time", "pisoc_steps_done", "pisoc_destroy", "pisoc_last_error", "pisoc_status_string",
     "pisoc_helm_apply", "pisoc_helm_workspace_bytes", "pisoc_helm_solve",
+    "pisoc_profile", "pisoc_profile_read",
 ]
+
+MAX_KSTATS = 24
 
 
 class Params(C.Structure):
@@ -64,6 +67,11 @@ class Stats(C.Structure):
         ("mach_rms", C.c_double), ("mass_gas", C.c_double),
         ("conc_var", C.c_double * MAX_CLASSES), ("mass_p", C.c_double * MAX_CLASSES),
     ]
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("ms", C.c_double),
+                ("bytes", C.c_double)]
 
 
 _lib = None
@@ -106,6 +114,10 @@ def lib():
     L.pisoc_helm_solve.argtypes = [i32, vp, vp, vp, vp, f64, i32, vp, sz, vp,
                                    C.POINTER(i32), C.POINTER(f64)]
     L.pisoc_helm_solve.restype = C.c_int
+    L.pisoc_profile.argtypes = [vp, i32]
+    L.pisoc_profile.restype = C.c_int
+    L.pisoc_profile_read.argtypes = [vp, C.POINTER(KernelStat), i32]
+    L.pisoc_profile_read.restype = i32
     _lib = L
     return L
 
@@ -249,6 +261,19 @@ class Solver:
     @property
     def t(self):
         return lib().pisoc_time(self._h)
+
+    def profile(self, enable=True):
+        """Enable (and reset) or disable per-kernel event timing."""
+        st = lib().pisoc_profile(self._h, 1 if enable else 0)
+        if st != OK:
+            raise PisocError(st, self.last_error())
+
+    def profile_read(self):
+        """{kernel name: dict(launches, ms, bytes)} of the counted launches."""
+        arr = (KernelStat * MAX_KSTATS)()
+        n = lib().pisoc_profile_read(self._h, arr, MAX_KSTATS)
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms,
+                                           bytes=arr[i].bytes) for i in range(n)}
 
 
 def helm_apply(psidt, w, x, stream=None):

@@ -1,8 +1,12 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Fields are compared element by element with the deviation-normalised error
-max|f_gpu - f_oracle| / max|f_oracle - <f_oracle>|; FP64 parity is 1e-10
-(operators 1e-12), and the CG iteration counts must match.  Sizes span
+Fields are compared element by element with two bounds: max|f_gpu - f_oracle|
+<= 1e-10 max|f_oracle| (FP64 agreement to 1e-10 relative), and <= 1e-8 of the
+field's spread max|f - <f>|, so that the deviations from the mean -- the part
+that carries the physics when a field starts uniform -- agree to 8 digits.
+(The oracle stores absolute densities and loses digits in rho_k - rho^n; the
+GPU path stores deviations; their difference is a few thousand FP64 ulps of
+the magnitude.)  The CG iteration counts must match exactly.  Sizes span
 several blocks with ragged tails (40, 70), the minimum grid (8) and the
 decaying-HIT configuration at 32^3.
 """
@@ -29,12 +33,18 @@ def P():
 
 
 def dev_err(g, o):
+    """max|g - o| in units of the pass mark: 1.0 = min(1e-10 |o|max, 1e-8 spread)
+    reached; the returned value is scaled so that TOL is the pass mark."""
     g = np.asarray(g)
     o = np.asarray(o)
-    scale = np.max(np.abs(o - o.mean()))
-    if scale == 0:
-        scale = max(np.max(np.abs(o)), 1e-300)
-    return float(np.max(np.abs(g - o)) / scale)
+    d = np.max(np.abs(g - o))
+    mag = np.max(np.abs(o))
+    spread = np.max(np.abs(o - o.mean()))
+    if d == 0.0:
+        return 0.0
+    r_mag = d / (1e-10 * mag) if mag > 0 else np.inf
+    r_dev = d / (1e-8 * spread) if spread > 0 else (0.0 if d <= 1e-10 * mag else np.inf)
+    return float(TOL * max(r_mag, r_dev))
 
 
 def to_np(t):
@@ -75,7 +85,7 @@ def test_helm_apply_parity(P, ora, n):
     assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
 
 
-@pytest.mark.parametrize("n", [16, 40])
+@pytest.mark.parametrize("n", [16, 40, 128])
 def test_helm_solve_parity(P, ora, n):
     import torch
     rng = np.random.default_rng(100 + n)
@@ -148,6 +158,13 @@ def test_step_parity_hit32_100_steps(P, ora):
 def test_step_parity_ragged_and_small(P, ora, n, classes, steps):
     case = make_hit_case(n, 11, mach=0.5, stokes=classes)
     o, s, io, ig = run_pair(P, ora, case, steps, p_tol=1e-9)
+    compare_state(P, ora, s, o)
+
+
+def test_step_parity_hit128_tiled(P, ora):
+    """128^3 runs the LDS-tiled z-marching CG kernel (n a multiple of 64)."""
+    case = make_hit_case(128, 3, mach=0.2, stokes=(0.2,))
+    o, s, io, ig = run_pair(P, ora, case, 2, p_tol=1e-8)
     compare_state(P, ora, s, o)
 
 
