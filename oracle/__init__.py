@@ -182,6 +182,45 @@ def pcg(psidt, K, b, x0=None, tol=1e-10, maxit=1000):
     return x, int(it), rel.value
 
 
+# ---------------------------------------------------------------- conv net
+NET_CH = (2, 16, 16, 16, 1)
+
+
+def conv_nweights():
+    return int(lib().ora_conv_nweights())
+
+
+def conv_layer_slices():
+    """Slices of each layer's [co][ci][27] block in the flat weight vector."""
+    out, off = [], 0
+    for l in range(4):
+        m = NET_CH[l] * NET_CH[l + 1] * 27
+        out.append(slice(off, off + m))
+        off += m
+    return out
+
+
+def conv_forward(w, x):
+    """x: [batch][n^3][2] (or [batch,n,n,n,2]); returns y [batch][n,n,n]."""
+    w = _f64(w); x = _f64(x)
+    batch = x.shape[0]
+    n = round((x.size // (2 * batch)) ** (1 / 3))
+    y = np.empty((batch, n, n, n))
+    lib().ora_conv_forward(n, batch, _p(w), _p(x), _p(y))
+    return y
+
+
+def conv_backward(w, x, t):
+    """Loss (mean squared error) and its gradient with respect to the weights."""
+    w = _f64(w); x = _f64(x); t = _f64(t)
+    batch = x.shape[0]
+    n = round((x.size // (2 * batch)) ** (1 / 3))
+    g = np.empty_like(w)
+    loss = C.c_double(0.0)
+    lib().ora_conv_backward(n, batch, _p(w), _p(x), _p(t), _p(g), C.byref(loss))
+    return loss.value, g
+
+
 # ---------------------------------------------------------------- whole step
 class Oracle:
     """One oracle simulation state (host memory, FP64)."""

@@ -111,6 +111,12 @@ int32_t ora_pcg(int32_t n, const double* psidt, const double* k0, const double* 
                 const double* k2, const double* b, double* x, double tol, int32_t maxit,
                 double* relres);
 
+/* ---- learned pressure-guess network (conv.c) ---- */
+int32_t ora_conv_nweights(void);
+int ora_conv_forward(int32_t n, int32_t batch, const double* w, const double* x, double* y);
+int ora_conv_backward(int32_t n, int32_t batch, const double* w, const double* x, const double* t,
+                      double* grad_w, double* loss);
+
 #ifdef __cplusplus
 }
 #endif
