@@ -92,8 +92,8 @@ typedef struct {
     int32_t p_maxit;           /* CG iteration cap per solve */
     int32_t precision;         /* PISOC_FP64 or PISOC_FP32_REFINED */
     int32_t guess;             /* PISOC_GUESS_ZERO or PISOC_GUESS_LEARNED */
-    const void* d_guess_weights; /* learned guess: device pointer to PISOC_GUESS_NWEIGHTS
-                                    floats (layer-major, see pisoc_guess_apply) */
+    const void* d_guess_weights; /* learned guess: device pointer to PISOC_NET_NWEIGHTS FP32
+                                    weights (layout at pisoc_net_forward); read at init */
     double inner_tol;          /* FP32_REFINED: relative tolerance of each inner FP32 solve */
     int32_t max_refine;        /* FP32_REFINED: cap on FP64 refinement rounds per solve */
     int32_t capture;           /* != 0: keep corrector-1 pressure system of the last step
@@ -209,6 +209,51 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
                               const double* d_b, double* d_x, double tol, int32_t maxit,
                               void* d_workspace, size_t ws_bytes, void* hip_stream,
                               int32_t* iters, double* relres);
+
+/* ---- learned initial guess of the pressure correction --------------------
+ * Not in the paper: a small network predicts the start of each pressure solve
+ * from the corrector's Jacobi-scaled continuity defect and the pressure of the
+ * current density iterate; CG then runs to the same ||r|| <= p_tol ||b|| as
+ * without it, so the guess can only save iterations.
+ *
+ * Network: four periodic 3x3x3 convolutions with 2 -> 16 -> 16 -> 16 -> 1
+ * channels, ReLU after the first three, no biases (cross-correlation):
+ *   out[co](x) = sum_ci sum_d W[co][ci][t(d)] in[ci](x + d),  d in {-1,0,1}^3,
+ *   t(d) = (dz+1)*9 + (dy+1)*3 + (dx+1).
+ * Weights: PISOC_NET_NWEIGHTS FP32 values, layer after layer, each layer as
+ * [co][ci][27].  Evaluation uses BF16 weights and activations with FP32
+ * accumulation on the matrix cores.  Grids need n % 16 == 0.
+ * Inputs: channel-last FP32 [batch][n^3][2]; outputs FP32 [batch][n^3].
+ * Input channels (pisoc_net_inputs): (b/diag(M))/s1 and (p0 - <p0>)/s2, s1, s2
+ * their r.m.s.; the target is p'/s1, and the guess is s1 times the output. */
+#define PISOC_NET_NWEIGHTS 15120
+
+size_t pisoc_net_workspace_bytes(int32_t n, int32_t batch);
+
+/* y = net(x) for a batch of grids.  Asynchronous. */
+pisoc_status pisoc_net_forward(int32_t n, int32_t batch, const float* d_w, const float* d_x,
+                               float* d_y, void* d_ws, size_t ws_bytes, void* hip_stream);
+
+/* Mean squared error loss of net(x) against t and its gradient with respect to
+ * the weights (d_grad: PISOC_NET_NWEIGHTS FP32, overwritten; summed over the
+ * batch deterministically).  h_loss (host, may be NULL) receives the loss;
+ * then the call synchronises. */
+pisoc_status pisoc_net_grad(int32_t n, int32_t batch, const float* d_w, const float* d_x,
+                            const float* d_t, float* d_grad, double* h_loss, void* d_ws,
+                            size_t ws_bytes, void* hip_stream);
+
+/* One Adam update of nw FP32 weights (step counts from 1).  Asynchronous. */
+pisoc_status pisoc_net_adam(int32_t nw, float* d_w, const float* d_g, float* d_m, float* d_v,
+                            int32_t step, float lr, float beta1, float beta2, float eps,
+                            void* hip_stream);
+
+/* Network inputs of one pressure system (FP64 n^3 device arrays b, diag, p0 as
+ * captured by pisoc_fields) into d_x (FP32 [n^3][2]); with d_psol non-NULL the
+ * training target p'/s1 into d_t.  h_scales (host, may be NULL) receives
+ * s1, s2; then the call synchronises.  d_ws: pisoc_helm_workspace_bytes(n). */
+pisoc_status pisoc_net_inputs(int32_t n, const double* d_b, const double* d_diag,
+                              const double* d_p0, const double* d_psol, float* d_x, float* d_t,
+                              double* h_scales, void* d_ws, size_t ws_bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -19,8 +19,8 @@ BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "pisoc.hip"]
-EXTRA_SOURCES = ["guess.hip", "ensemble.hip"]   # compiled when present
+SOURCES = ["kernels.hip", "pisoc.hip", "net.hip"]
+EXTRA_SOURCES = ["ensemble.hip"]   # compiled when present
 
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-I", INCLUDE,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

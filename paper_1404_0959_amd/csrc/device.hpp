@@ -183,6 +183,14 @@ __device__ inline void reduce_partials(const double* __restrict__ part, unsigned
     for (int c = 0; c < NV; ++c) out[c] = tot[c];
 }
 
+// Round to nearest even FP32 -> BF16 (bit pattern); NaN stays NaN.
+__host__ __device__ inline uint16_t f2bf(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 // Pressure deviation p(rho) - p_ref for rho = rho_ref + r, written with
 // log1p/expm1 so that it stays accurate for small r in FP32.
 __device__ inline double pdev(double r, const Phys& ph) {

@@ -566,6 +566,132 @@ __global__ void __launch_bounds__(kBlock) k_helm_start(Phys ph, DevState* st,
     }
 }
 
+// ---------------------------------------------------------------- learned guess
+// Partial sums for the network's input scaling: sum (b/diag)^2, sum p0, sum p0^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_net_stats(Phys ph, const T* __restrict__ b,
+                                                      const T* __restrict__ diag,
+                                                      const T* __restrict__ p0, double* part) {
+    double v[3] = {0.0, 0.0, 0.0};
+    FOR_CELLS(ph)
+    const double z = (double)b[P] / (double)diag[P];
+    const double p = (double)p0[P];
+    v[0] += z * z;
+    v[1] += p;
+    v[2] += p * p;
+    END_CELLS
+    block_partials<3, 0u>(v, part);
+}
+
+// Network inputs: channel 0 = (b/diag)/s1, channel 1 = (p0 - <p0>)/s2 with s1, s2
+// their r.m.s. (the Jacobi-scaled continuity defect and the pressure of the
+// current density iterate, each normalised); BF16 [cell][4] and/or FP32
+// [cell][2]; with psol the training target psol/s1.  s1, s2 go to st->red[6..7].
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_net_input(Phys ph, DevState* st, const double* part,
+                                                      unsigned nb, const T* __restrict__ b,
+                                                      const T* __restrict__ diag,
+                                                      const T* __restrict__ p0,
+                                                      uint16_t* __restrict__ x4, float* __restrict__ x2,
+                                                      const T* __restrict__ psol,
+                                                      float* __restrict__ tgt) {
+    double t[3];
+    reduce_partials<3, 0u>(part, nb, t);
+    const double N = (double)ncell(ph);
+    const double s1 = sqrt(t[0] / N);
+    const double mean = t[1] / N;
+    const double var = t[2] / N - mean * mean;
+    const double s2 = var > 0.0 ? sqrt(var) : 0.0;
+    const double i1 = s1 > 0.0 ? 1.0 / s1 : 0.0, i2 = s2 > 0.0 ? 1.0 / s2 : 0.0;
+    if (st && flat_bid() == 0 && flat_tid() == 0) {
+        st->red[6] = s1;
+        st->red[7] = s2;
+    }
+    FOR_CELLS(ph)
+    const float c0 = (float)((double)b[P] / (double)diag[P] * i1);
+    const float c1 = (float)(((double)p0[P] - mean) * i2);
+    if (x4) {
+        x4[4 * P + 0] = f2bf(c0);
+        x4[4 * P + 1] = f2bf(c1);
+        x4[4 * P + 2] = 0;
+        x4[4 * P + 3] = 0;
+    }
+    if (x2) {
+        x2[2 * P + 0] = c0;
+        x2[2 * P + 1] = c1;
+    }
+    if (tgt) tgt[P] = (float)((double)psol[P] * i1);
+    END_CELLS
+}
+
+// Start CG from the network's guess x0 = s1 y: r = b - M x0 (difference form,
+// FP64 arithmetic), b kept in bsave for a fallback.  FP64 storage: x = x0.
+// FP32 storage (x64 non-null): the FP64 accumulator x64 = x0 and the inner
+// correction x = 0.  Partial sums r.(r/diag), ||r0||^2, ||b||^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_guess_start(Phys ph, DevState* st,
+                                                        const float* __restrict__ y,
+                                                        const T* __restrict__ w,
+                                                        const T* __restrict__ diag, T* __restrict__ r,
+                                                        T* __restrict__ x, double* __restrict__ x64,
+                                                        const double* __restrict__ b64,
+                                                        T* __restrict__ bsave, double* part_u) {
+    const double s1 = st->red[6], inv_h2 = ph.inv_h2;
+    double v[3] = {0.0, 0.0, 0.0};
+    FOR_CELLS(ph)
+    auto g = [&](size_t Q) { return s1 * (double)y[Q]; };
+    const double gP = g(P);
+    double lap = 0.0, sumK = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double kp = i4r<double>(w, c, d, 0), km = i4r<double>(w, c, d, -1);
+        lap += kp * (gP - g(c.sh(d, 1))) + km * (gP - g(c.sh(d, -1)));
+        sumK += kp + km;
+    }
+    const double bP = b64 ? b64[P] : (double)r[P];
+    const double r0 = bP - (((double)diag[P] - sumK * inv_h2) * gP + lap * inv_h2);
+    bsave[P] = r[P];
+    const T rT = (T)r0;
+    r[P] = rT;
+    if (x64) {
+        x64[P] = gP;
+        x[P] = T(0);
+    } else {
+        x[P] = (T)gP;
+    }
+    v[0] += (double)rT * ((double)rT / (double)diag[P]);
+    v[1] += r0 * r0;
+    v[2] += bP * bP;
+    END_CELLS
+    block_partials<3, 0u>(v, part_u);
+    if (flat_bid() == 0 && flat_tid() == 0) {
+        st->pcg.it_stop = kIterInf;
+        st->pcg.converged = 0;
+        st->pcg.iters = 0;
+    }
+}
+
+// Fallback to the zero guess: r = b, x = 0 (and x64 = 0), partials as corr_rhs.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_guess_revert(Phys ph, T* __restrict__ r,
+                                                         T* __restrict__ x, double* __restrict__ x64,
+                                                         const double* __restrict__ b64,
+                                                         const T* __restrict__ bsave,
+                                                         const T* __restrict__ diag, double* part_u) {
+    double v[3] = {0.0, 0.0, 0.0};
+    FOR_CELLS(ph)
+    const T bT = bsave[P];
+    r[P] = bT;
+    x[P] = T(0);
+    if (x64) x64[P] = 0.0;
+    const double bd = (double)bT, bb = b64 ? b64[P] : bd;
+    v[0] += bd * (bd / (double)diag[P]);
+    v[1] += bb * bb;
+    v[2] += bb * bb;
+    END_CELLS
+    block_partials<3, 0u>(v, part_u);
+}
+
 // ---------------------------------------------------------------- correction
 // p = p0 + p'; corrected face fluxes phi = phiH - K A snGrad(p) on own faces.
 template <typename T>
@@ -989,6 +1115,29 @@ void step_finish(hipStream_t s, const Phys& ph, DevState* st, const double* part
                  const double* part_dust, int ncls, unsigned nb, size_t cls_stride) {
     hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(64, 4), 0, s, ph, st, part_mass, part_dust,
                        ncls, nb, cls_stride);
+}
+
+template <typename T>
+void Ops<T>::net_stats(const Launch& L, hipStream_t s, const Phys& ph, const T* b, const T* diag,
+                       const T* p0, double* part) {
+    LAUNCH(k_net_stats<T>, L, s, ph, b, diag, p0, part);
+}
+template <typename T>
+void Ops<T>::net_input(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
+                       const double* part, const T* b, const T* diag, const T* p0, uint16_t* x4,
+                       float* x2, const T* psol, float* tgt) {
+    LAUNCH(k_net_input<T>, L, s, ph, st, part, L.nblocks, b, diag, p0, x4, x2, psol, tgt);
+}
+template <typename T>
+void Ops<T>::guess_start(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
+                         const float* y, const T* w, const T* diag, T* r, T* x, double* x64,
+                         const double* b64, T* bsave, double* part_u) {
+    LAUNCH(k_guess_start<T>, L, s, ph, st, y, w, diag, r, x, x64, b64, bsave, part_u);
+}
+template <typename T>
+void Ops<T>::guess_revert(const Launch& L, hipStream_t s, const Phys& ph, T* r, T* x, double* x64,
+                          const double* b64, const T* bsave, const T* diag, double* part_u) {
+    LAUNCH(k_guess_revert<T>, L, s, ph, r, x, x64, b64, bsave, diag, part_u);
 }
 
 template struct Ops<double>;

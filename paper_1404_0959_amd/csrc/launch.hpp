@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
 
 #include "device.hpp"
 
@@ -98,6 +99,18 @@ struct Ops {
                           double* part);
     static void sum_affine_sq(const Launch& L, hipStream_t s, const Phys& ph, const T* x,
                               double a, double b, double* part);
+    // learned guess
+    static void net_stats(const Launch& L, hipStream_t s, const Phys& ph, const T* b,
+                          const T* diag, const T* p0, double* part);
+    static void net_input(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
+                          const double* part, const T* b, const T* diag, const T* p0,
+                          uint16_t* x4, float* x2, const T* psol, float* tgt);
+    static void guess_start(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
+                            const float* y, const T* w, const T* diag, T* r, T* x, double* x64,
+                            const double* b64, T* bsave, double* part_u);
+    static void guess_revert(const Launch& L, hipStream_t s, const Phys& ph, T* r, T* x,
+                             double* x64, const double* b64, const T* bsave, const T* diag,
+                             double* part_u);
 };
 
 // One-block totals of nv partial columns into dst (device).

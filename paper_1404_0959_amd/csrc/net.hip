@@ -1,0 +1,463 @@
+// net.hip -- the learned pressure-guess network on gfx950: four periodic
+// 3x3x3 convolutions (2 -> 16 -> 16 -> 16 -> 1, ReLU after the first three, no
+// biases) evaluated with BF16 operands and FP32 accumulation on the matrix
+// cores (v_mfma_f32_16x16x16_bf16), plus the training kernels (data and weight
+// gradients, MSE loss, Adam) and the C ABI of the network.
+//
+// GEMM view of one layer: for 16 consecutive cells along x (one wavefront),
+// D[cell][co] = sum over K of A[cell][k] B[k][co] with k = (tap, ci).  With 16
+// input channels a K-block of 16 is one tap; with 4 (padded) input channels a
+// K-block holds 4 taps.  Lane l loads 4 consecutive channels (8 bytes) of one
+// neighbour cell, so activations are stored channel-last in BF16.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "../../include/pisoc.h"
+#include "device.hpp"
+#include "launch.hpp"
+#include "net.hpp"
+
+namespace pisoc {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ inline float bf2f(uint16_t b) {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+__device__ inline int wrapn(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+template <int CINP> constexpr int nkb() { return CINP == 16 ? 27 : 7; }
+
+// (tap, channel) of entry kk (0..15) of K-block kb.
+template <int CINP>
+__host__ __device__ inline void kdecode(int kb, int kk, int& tap, int& ch) {
+    if (CINP == 16) {
+        tap = kb;
+        ch = kk;
+    } else {
+        tap = 4 * kb + kk / 4;
+        ch = kk % 4;
+    }
+}
+
+// One convolution layer on a channel-last BF16 input with CINP channels.
+// Output: BF16 [cell][16] (ReLU, or masked by mask > 0 for a data gradient), or
+// with FINAL the FP32 channel 0 times yscale.
+template <int CINP, bool FINAL>
+__global__ void __launch_bounds__(256) k_conv(int n, int batch, const uint16_t* __restrict__ in,
+                                              const v4s* __restrict__ wpk,
+                                              const uint16_t* __restrict__ mask, int relu,
+                                              uint16_t* __restrict__ out, float* __restrict__ yout,
+                                              float yscale) {
+    constexpr int NKB = nkb<CINP>();
+    const int lane = threadIdx.x & 63;
+    const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int segs = n / 16;
+    const long nseg = (long)batch * n * n * segs;
+    if (wave >= nseg) return;  // whole wavefront; no block barrier below
+    const int iseg = (int)(wave % segs);
+    long rest = wave / segs;
+    const int j = (int)(rest % n);
+    rest /= n;
+    const int k = (int)(rest % n);
+    const int b = (int)(rest / n);
+    const size_t N = (size_t)n * n * n;
+    const int m = lane & 15, g = lane >> 4;
+    const int i = iseg * 16 + m;
+    v4s B[NKB];
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) B[kb] = wpk[kb * 64 + lane];
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+        const int tap = CINP == 16 ? kb : 4 * kb + g;
+        v4s a = {0, 0, 0, 0};
+        if (tap < 27) {
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const size_t cell = (size_t)wrapn(i + dx, n) +
+                                (size_t)n * ((size_t)wrapn(j + dy, n) + (size_t)n * wrapn(k + dz, n));
+            const int c0 = CINP == 16 ? 4 * g : 0;
+            a = *reinterpret_cast<const v4s*>(in + ((size_t)b * N + cell) * CINP + c0);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, B[kb], acc, 0, 0, 0);
+    }
+    // lane holds D[4g + e][lane & 15]
+    const int nn = lane & 15;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const size_t cell = (size_t)(iseg * 16 + 4 * g + e) + (size_t)n * ((size_t)j + (size_t)n * k);
+        const size_t P = (size_t)b * N + cell;
+        float v = acc[e];
+        if (FINAL) {
+            if (nn == 0) yout[P] = v * yscale;
+        } else {
+            if (mask) {
+                const uint16_t mb = mask[P * 16 + nn];
+                if (!((mb & 0x7fffu) != 0 && (mb & 0x8000u) == 0)) v = 0.f;
+            } else if (relu) {
+                v = v > 0.f ? v : 0.f;
+            }
+            out[P * 16 + nn] = f2bf(v);
+        }
+    }
+}
+
+// Weight gradient of one layer: partial sums over this wavefront's cells of
+// D[co][(tap, ci)] = sum_cells g[cell][co] in[cell + d(tap)][ci], one 16x16 tile
+// per K-block, written to part[wave][kb][co][n].
+template <int CINP>
+__global__ void __launch_bounds__(256) k_conv_wgrad(int n, int batch,
+                                                    const uint16_t* __restrict__ in,
+                                                    const uint16_t* __restrict__ gr, int gp,
+                                                    int cout, float* __restrict__ part, int spw,
+                                                    int nwaves) {
+    constexpr int NKB = nkb<CINP>();
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= nwaves) return;
+    const int segs = n / 16;
+    const long nseg = (long)batch * n * n * segs;
+    const size_t N = (size_t)n * n * n;
+    const int m = lane & 15, g = lane >> 4, nn = lane & 15;
+    v4f acc[NKB];
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) acc[kb] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (long s = (long)wave * spw; s < (long)(wave + 1) * spw && s < nseg; ++s) {
+        const int iseg = (int)(s % segs);
+        long rest = s / segs;
+        const int j = (int)(rest % n);
+        rest /= n;
+        const int k = (int)(rest % n);
+        const int b = (int)(rest / n);
+        v4s a;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const size_t P = (size_t)b * N + (size_t)(iseg * 16 + 4 * g + e) +
+                             (size_t)n * ((size_t)j + (size_t)n * k);
+            a[e] = m < cout ? (short)gr[P * gp + m] : (short)0;
+        }
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) {
+            int tap, ci;
+            kdecode<CINP>(kb, nn, tap, ci);
+            v4s bb = {0, 0, 0, 0};
+            if (tap < 27) {
+                const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+                const size_t yz = (size_t)n * ((size_t)wrapn(j + dy, n) + (size_t)n * wrapn(k + dz, n));
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const size_t cell = (size_t)wrapn(iseg * 16 + 4 * g + e + dx, n) + yz;
+                    bb[e] = (short)in[((size_t)b * N + cell) * CINP + ci];
+                }
+            }
+            acc[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[kb], 0, 0, 0);
+        }
+    }
+    float* dst = part + (size_t)wave * NKB * 256;
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[kb * 256 + (4 * g + e) * 16 + nn] = acc[kb][e];
+}
+
+// Sum the per-wavefront partials in wavefront order and scatter them into the
+// FP32 gradient layout [co][ci][27] of one layer (deterministic).
+template <int CINP>
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int nwaves, int cin, int cout,
+                               float* __restrict__ grad) {
+    constexpr int NKB = nkb<CINP>();
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= NKB * 256) return;
+    const int kb = idx / 256, co = (idx % 256) / 16, nn = idx % 16;
+    int tap, ci;
+    kdecode<CINP>(kb, nn, tap, ci);
+    if (tap >= 27 || ci >= cin || co >= cout) return;
+    double s = 0.0;
+    for (int w = 0; w < nwaves; ++w) s += (double)part[(size_t)w * NKB * 256 + idx];
+    grad[((size_t)co * cin + ci) * 27 + tap] = (float)s;
+}
+
+// Pack one layer's FP32 weights [co][ci][27] into per-lane BF16 B operands.
+// Forward: out channel n = co, K entry (tap, ci).  Data gradient (tflip): out
+// channel n = ci, K entry (tap', co) with weight W[co][ci][26 - tap'].
+template <int CINP>
+__global__ void k_pack(const float* __restrict__ w, int cin, int cout, int tflip,
+                       v4s* __restrict__ wpk) {
+    constexpr int NKB = nkb<CINP>();
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NKB * 64) return;
+    const int kb = t / 64, lane = t % 64;
+    const int nn = lane & 15, g = lane >> 4;
+    v4s v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        int tap, cc;
+        kdecode<CINP>(kb, 4 * g + e, tap, cc);
+        float x = 0.f;
+        if (tap < 27) {
+            if (!tflip) {
+                if (nn < cout && cc < cin) x = w[((size_t)nn * cin + cc) * 27 + tap];
+            } else {
+                if (nn < cin && cc < cout) x = w[((size_t)cc * cin + nn) * 27 + (26 - tap)];
+            }
+        }
+        v[e] = (short)f2bf(x);
+    }
+    wpk[t] = v;
+}
+
+// Network input: channel-last BF16 [cell][4] = (x0, x1, 0, 0) from FP32 [cell][2].
+__global__ void k_input_bf16(const float* __restrict__ x, uint16_t* __restrict__ xb, size_t cells) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < cells; i += stride) {
+        xb[4 * i + 0] = f2bf(x[2 * i + 0]);
+        xb[4 * i + 1] = f2bf(x[2 * i + 1]);
+        xb[4 * i + 2] = 0;
+        xb[4 * i + 3] = 0;
+    }
+}
+
+// MSE loss partials and the output gradient dy = 2 (y - t) / count as BF16 [cell][4].
+__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ y, const float* __restrict__ t,
+                                             size_t count, float scale, uint16_t* __restrict__ dy,
+                                             double* part) {
+    double v[1] = {0.0};
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) {
+        const float d = y[i] - t[i];
+        v[0] += (double)d * (double)d;
+        dy[4 * i + 0] = f2bf(scale * d);
+        dy[4 * i + 1] = 0;
+        dy[4 * i + 2] = 0;
+        dy[4 * i + 3] = 0;
+    }
+    block_partials<1, 0u>(v, part);
+}
+
+__global__ void k_adam(int nw, float* __restrict__ w, const float* __restrict__ g,
+                       float* __restrict__ m, float* __restrict__ v, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------
+static const int kCh[5] = {2, 16, 16, 16, 1};
+
+size_t net_weight_offset(int layer) {
+    size_t s = 0;
+    for (int l = 0; l < layer; ++l) s += (size_t)kCh[l] * kCh[l + 1] * 27;
+    return s;
+}
+
+size_t net_packed_bytes() { return (size_t)(7 + 27 + 27 + 27) * 64 * sizeof(v4s); }
+
+void net_pack_forward(hipStream_t s, const float* w32, void* wpk) {
+    v4s* p = reinterpret_cast<v4s*>(wpk);
+    hipLaunchKernelGGL(k_pack<4>, dim3((7 * 64 + 255) / 256), dim3(256), 0, s,
+                       w32 + net_weight_offset(0), 2, 16, 0, p);
+    p += 7 * 64;
+    for (int l = 1; l < 4; ++l) {
+        hipLaunchKernelGGL(k_pack<16>, dim3((27 * 64 + 255) / 256), dim3(256), 0, s,
+                           w32 + net_weight_offset(l), 16, kCh[l + 1], 0, p);
+        p += 27 * 64;
+    }
+}
+
+static dim3 conv_grid(int n, int batch) {
+    const long waves = (long)batch * n * n * (n / 16);
+    return dim3((unsigned)((waves + 3) / 4));
+}
+
+void net_forward(hipStream_t s, int n, int batch, const void* wpk, const uint16_t* x4,
+                 uint16_t* a, uint16_t* b, float* y, float yscale) {
+    const v4s* p = reinterpret_cast<const v4s*>(wpk);
+    const dim3 G = conv_grid(n, batch), B(256);
+    hipLaunchKernelGGL((k_conv<4, false>), G, B, 0, s, n, batch, x4, p, (const uint16_t*)nullptr, 1, a,
+                       (float*)nullptr, 1.f);
+    p += 7 * 64;
+    hipLaunchKernelGGL((k_conv<16, false>), G, B, 0, s, n, batch, a, p, (const uint16_t*)nullptr, 1, b,
+                       (float*)nullptr, 1.f);
+    p += 27 * 64;
+    hipLaunchKernelGGL((k_conv<16, false>), G, B, 0, s, n, batch, b, p, (const uint16_t*)nullptr, 1, a,
+                       (float*)nullptr, 1.f);
+    p += 27 * 64;
+    hipLaunchKernelGGL((k_conv<16, true>), G, B, 0, s, n, batch, a, p, (const uint16_t*)nullptr, 0,
+                       (uint16_t*)nullptr, y, yscale);
+}
+
+// ---- training workspace ----
+struct NetWs {
+    size_t x4, a1, a2, a3, y, g1, g2, dy, wf, wb, part, lpart, total;
+    int nwaves, spw;
+    unsigned lblocks;
+};
+
+static NetWs net_layout(int n, int batch) {
+    NetWs L{};
+    const size_t cells = (size_t)batch * n * n * n;
+    const long nseg = (long)batch * n * n * (n / 16);
+    L.nwaves = (int)(nseg < 1024 ? nseg : 1024);
+    L.spw = (int)((nseg + L.nwaves - 1) / L.nwaves);
+    L.lblocks = 1024;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = (off + bytes + 255) / 256 * 256;
+        return o;
+    };
+    L.x4 = take(cells * 4 * 2);
+    L.a1 = take(cells * 16 * 2);
+    L.a2 = take(cells * 16 * 2);
+    L.a3 = take(cells * 16 * 2);
+    L.y = take(cells * 4);
+    L.g1 = take(cells * 16 * 2);
+    L.g2 = take(cells * 16 * 2);
+    L.dy = take(cells * 4 * 2);
+    L.wf = take(net_packed_bytes());
+    L.wb = take((size_t)3 * 27 * 64 * sizeof(v4s));
+    L.part = take((size_t)L.nwaves * 27 * 256 * sizeof(float));
+    L.lpart = take((size_t)L.lblocks * sizeof(double) + sizeof(double));
+    L.total = off;
+    return L;
+}
+
+}  // namespace pisoc
+
+using namespace pisoc;
+
+static bool net_shape_ok(int32_t n, int32_t batch) {
+    return n >= 16 && n <= PISOC_MAX_N && n % 16 == 0 && batch >= 1;
+}
+
+extern "C" {
+
+size_t pisoc_net_workspace_bytes(int32_t n, int32_t batch) {
+    if (!net_shape_ok(n, batch)) return 0;
+    return net_layout(n, batch).total;
+}
+
+pisoc_status pisoc_net_forward(int32_t n, int32_t batch, const float* d_w, const float* d_x,
+                               float* d_y, void* d_ws, size_t ws_bytes, void* stream) {
+    if (!net_shape_ok(n, batch) || !d_w || !d_x || !d_y) return PISOC_ERR_INVALID;
+    NetWs L = net_layout(n, batch);
+    if (!d_ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(d_ws) % 256) != 0)
+        return PISOC_ERR_WORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* ws = reinterpret_cast<char*>(d_ws);
+    const size_t cells = (size_t)batch * n * n * n;
+    uint16_t* x4 = reinterpret_cast<uint16_t*>(ws + L.x4);
+    hipLaunchKernelGGL(k_input_bf16, dim3((unsigned)std::min<size_t>((cells + 255) / 256, 65536)),
+                       dim3(256), 0, s, d_x, x4, cells);
+    net_pack_forward(s, d_w, ws + L.wf);
+    net_forward(s, n, batch, ws + L.wf, x4, reinterpret_cast<uint16_t*>(ws + L.a1),
+                reinterpret_cast<uint16_t*>(ws + L.a2), d_y, 1.f);
+    return hipGetLastError() == hipSuccess ? PISOC_OK : PISOC_ERR_HIP;
+}
+
+pisoc_status pisoc_net_grad(int32_t n, int32_t batch, const float* d_w, const float* d_x,
+                            const float* d_t, float* d_grad, double* h_loss, void* d_ws,
+                            size_t ws_bytes, void* stream) {
+    if (!net_shape_ok(n, batch) || !d_w || !d_x || !d_t || !d_grad) return PISOC_ERR_INVALID;
+    NetWs L = net_layout(n, batch);
+    if (!d_ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(d_ws) % 256) != 0)
+        return PISOC_ERR_WORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* ws = reinterpret_cast<char*>(d_ws);
+    auto U = [&](size_t off) { return reinterpret_cast<uint16_t*>(ws + off); };
+    const size_t cells = (size_t)batch * n * n * n;
+    const dim3 G = conv_grid(n, batch), B(256);
+    const unsigned lin = (unsigned)std::min<size_t>((cells + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_input_bf16, dim3(lin), B, 0, s, d_x, U(L.x4), cells);
+    net_pack_forward(s, d_w, ws + L.wf);
+    // data-gradient weights of layers 2..4 (transposed, flipped)
+    v4s* wb = reinterpret_cast<v4s*>(ws + L.wb);
+    for (int l = 1; l < 4; ++l) {
+        if (l == 3)
+            hipLaunchKernelGGL(k_pack<4>, dim3((7 * 64 + 255) / 256), B, 0, s,
+                               d_w + net_weight_offset(l), 16, 1, 1, wb + (l - 1) * 27 * 64);
+        else
+            hipLaunchKernelGGL(k_pack<16>, dim3((27 * 64 + 255) / 256), B, 0, s,
+                               d_w + net_weight_offset(l), 16, 16, 1, wb + (l - 1) * 27 * 64);
+    }
+    // forward keeping every activation
+    const v4s* wf = reinterpret_cast<const v4s*>(ws + L.wf);
+    float* y = reinterpret_cast<float*>(ws + L.y);
+    hipLaunchKernelGGL((k_conv<4, false>), G, B, 0, s, n, batch, U(L.x4), wf, (const uint16_t*)nullptr,
+                       1, U(L.a1), (float*)nullptr, 1.f);
+    hipLaunchKernelGGL((k_conv<16, false>), G, B, 0, s, n, batch, U(L.a1), wf + 7 * 64,
+                       (const uint16_t*)nullptr, 1, U(L.a2), (float*)nullptr, 1.f);
+    hipLaunchKernelGGL((k_conv<16, false>), G, B, 0, s, n, batch, U(L.a2), wf + 34 * 64,
+                       (const uint16_t*)nullptr, 1, U(L.a3), (float*)nullptr, 1.f);
+    hipLaunchKernelGGL((k_conv<16, true>), G, B, 0, s, n, batch, U(L.a3), wf + 61 * 64,
+                       (const uint16_t*)nullptr, 0, (uint16_t*)nullptr, y, 1.f);
+    // loss and output gradient
+    double* lpart = reinterpret_cast<double*>(ws + L.lpart);
+    hipLaunchKernelGGL(k_mse, dim3(L.lblocks), B, 0, s, y, d_t, cells, (float)(2.0 / (double)cells),
+                       U(L.dy), lpart);
+    double* loss_dev = lpart + L.lblocks;
+    finalize_sums(s, lpart, L.lblocks, 1, loss_dev);
+    // backward: layer 4 (linear), 3, 2, 1
+    float* part = reinterpret_cast<float*>(ws + L.part);
+    const dim3 GW((L.nwaves + 3) / 4);
+    auto wgrad16 = [&](const uint16_t* in, const uint16_t* gr, int gp, int cout, int layer) {
+        hipLaunchKernelGGL(k_conv_wgrad<16>, GW, B, 0, s, n, batch, in, gr, gp, cout, part, L.spw,
+                           L.nwaves);
+        hipLaunchKernelGGL(k_wgrad_reduce<16>, dim3((27 * 256 + 255) / 256), B, 0, s, part, L.nwaves,
+                           16, cout, d_grad + net_weight_offset(layer));
+    };
+    wgrad16(U(L.a3), U(L.dy), 4, 1, 3);
+    hipLaunchKernelGGL((k_conv<4, false>), G, B, 0, s, n, batch, U(L.dy), wb + 2 * 27 * 64, U(L.a3),
+                       0, U(L.g1), (float*)nullptr, 1.f);
+    wgrad16(U(L.a2), U(L.g1), 16, 16, 2);
+    hipLaunchKernelGGL((k_conv<16, false>), G, B, 0, s, n, batch, U(L.g1), wb + 27 * 64, U(L.a2), 0,
+                       U(L.g2), (float*)nullptr, 1.f);
+    wgrad16(U(L.a1), U(L.g2), 16, 16, 1);
+    hipLaunchKernelGGL((k_conv<16, false>), G, B, 0, s, n, batch, U(L.g2), wb, U(L.a1), 0, U(L.g1),
+                       (float*)nullptr, 1.f);
+    hipLaunchKernelGGL(k_conv_wgrad<4>, GW, B, 0, s, n, batch, U(L.x4), U(L.g1), 16, 16, part, L.spw,
+                       L.nwaves);
+    hipLaunchKernelGGL(k_wgrad_reduce<4>, dim3((7 * 256 + 255) / 256), B, 0, s, part, L.nwaves, 2, 16,
+                       d_grad + net_weight_offset(0));
+    if (hipGetLastError() != hipSuccess) return PISOC_ERR_HIP;
+    if (h_loss) {
+        double l = 0.0;
+        if (hipMemcpyAsync(&l, loss_dev, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return PISOC_ERR_HIP;
+        *h_loss = l / (double)cells;
+    }
+    return PISOC_OK;
+}
+
+pisoc_status pisoc_net_adam(int32_t nw, float* d_w, const float* d_g, float* d_m, float* d_v,
+                            int32_t step, float lr, float beta1, float beta2, float eps,
+                            void* stream) {
+    if (nw < 1 || !d_w || !d_g || !d_m || !d_v || step < 1) return PISOC_ERR_INVALID;
+    const float c1 = 1.f - std::pow(beta1, (float)step), c2 = 1.f - std::pow(beta2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((nw + 255) / 256), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), nw, d_w, d_g, d_m, d_v, lr, beta1,
+                       beta2, eps, c1, c2);
+    return hipGetLastError() == hipSuccess ? PISOC_OK : PISOC_ERR_HIP;
+}
+
+}  // extern "C"

@@ -20,6 +20,7 @@
 #include "../../include/pisoc.h"
 #include "device.hpp"
 #include "launch.hpp"
+#include "net.hpp"
 
 using namespace pisoc;
 
@@ -38,6 +39,7 @@ struct Layout {
     size_t rhop, rhop1;
     size_t snap;   // 4 FP64 fields when capturing
     size_t b64, x64a, x64b;  // FP64 refinement fields (FP32 storage only)
+    size_t wpk, nx4, na, nb, ny, bsave;  // learned guess: packed weights, activations
     size_t total;
     unsigned max_blocks;
 };
@@ -47,12 +49,12 @@ struct Layout {
 enum KCls {
     KC_CFL, KC_PREDICT, KC_MOM_SOURCE, KC_MOM_SWEEP, KC_HBYA, KC_CORR_RHS, KC_PCG_SPMV,
     KC_PCG_UPDATE, KC_CORR_FLUX, KC_CORR_UPDATE, KC_DUDT, KC_DUST_FLUX, KC_DUST_SWEEP,
-    KC_DUST_FACEFLUX, KC_DUST_FINISH, KC_REFINE, KC_COUNT
+    KC_DUST_FACEFLUX, KC_DUST_FINISH, KC_REFINE, KC_NET, KC_COUNT
 };
 const char* const kKernelName[KC_COUNT] = {
     "k_cfl", "k_predict", "k_mom_source", "k_mom_sweep", "k_hbya", "k_corr_rhs",
     "k_pcg_spmv", "k_pcg_update", "k_corr_flux", "k_corr_update", "k_dudt", "k_dust_flux",
-    "k_dust_sweep", "k_dust_faceflux", "k_dust_finish", "k_refine"};
+    "k_dust_sweep", "k_dust_faceflux", "k_dust_finish", "k_refine", "learned_guess"};
 
 struct Prof {
     bool on = false;
@@ -113,7 +115,9 @@ bool valid_params(const pisoc_params* p, std::string* why) {
     if (p->precision == PISOC_FP32_REFINED &&
         (!(p->inner_tol > 0.0) || !(p->inner_tol < 1.0) || p->max_refine < 1))
         return fail("FP32_REFINED needs 0 < inner_tol < 1 and max_refine >= 1");
-    if (p->guess != PISOC_GUESS_ZERO) return fail("learned guess is not built yet");
+    if (p->guess != PISOC_GUESS_ZERO && p->guess != PISOC_GUESS_LEARNED) return fail("unknown guess");
+    if (p->guess == PISOC_GUESS_LEARNED && (!p->d_guess_weights || p->n % 16 != 0))
+        return fail("learned guess needs d_guess_weights and n % 16 == 0");
     return true;
 }
 
@@ -136,6 +140,14 @@ Layout make_layout(const pisoc_params* p) {
     L.rhop = take(es * N * (size_t)std::max(p->n_classes, 1));
     L.rhop1 = take(es * N * (size_t)std::max(p->n_classes, 1));
     L.snap = p->capture ? take(4 * sizeof(double) * N) : 0;
+    if (p->guess == PISOC_GUESS_LEARNED) {
+        L.wpk = take(net_packed_bytes());
+        L.nx4 = take(4 * 2 * N);
+        L.na = take(16 * 2 * N);
+        L.nb = take(16 * 2 * N);
+        L.ny = take(4 * N);
+        L.bsave = take(es * N);
+    }
     if (p->precision == PISOC_FP32_REFINED) {
         L.b64 = take(sizeof(double) * N);
         L.x64a = take(sizeof(double) * N);
@@ -338,6 +350,41 @@ pisoc_status refine_solve(pisoc_ctx* ctx, float* r, float* x, float* diag, float
     return PISOC_OK;
 }
 
+// The learned initial guess of one pressure solve: scaled inputs from the
+// system just set up, the network on the matrix cores, CG restarted from
+// x0 = s1 y; rejected (back to x0 = 0) unless ||b - M x0|| < ||b||.
+template <typename T>
+pisoc_status learned_guess(pisoc_ctx* ctx, T* r, T* x, T* dg, T* w, T* p0, int* flags) {
+    using O = Ops<T>;
+    const Layout& Y = ctx->lay;
+    const bool f32 = sizeof(T) == sizeof(float);
+    hipStream_t s = ctx->stream;
+    double* x64 = f32 ? ctx->f<double>(Y.x64a) : nullptr;
+    double* b64 = f32 ? ctx->f<double>(Y.b64) : nullptr;
+    T* bsave = ctx->f<T>(Y.bsave);
+    timed(ctx, KC_NET, 2, -1, [&] {
+        O::net_stats(ctx->L, s, ctx->ph, r, dg, p0, ctx->part(PS_STAT));
+        O::net_input(ctx->L, s, ctx->ph, ctx->st, ctx->part(PS_STAT), r, dg, p0,
+                     ctx->f<uint16_t>(Y.nx4), nullptr, nullptr, nullptr);
+        net_forward(s, ctx->prm.n, 1, ctx->ws + Y.wpk, ctx->f<uint16_t>(Y.nx4),
+                    ctx->f<uint16_t>(Y.na), ctx->f<uint16_t>(Y.nb), ctx->f<float>(Y.ny), 1.f);
+        O::guess_start(ctx->L, s, ctx->ph, ctx->st, ctx->f<float>(Y.ny), w, dg, r, x, x64, b64,
+                       bsave, ctx->part(PS_U));
+    });
+    // totals of r0.z0, ||r0||^2, ||b||^2 (3 columns written with L.nblocks blocks)
+    const unsigned nb = ctx->L.nblocks;
+    finalize_sums(s, ctx->part(PS_U), nb, 3, ctx->st->red);
+    pisoc_status st = sync_state(ctx);
+    if (st != PISOC_OK) return st;
+    if (ctx->prof.on) ctx->prof.resolve(kIterInf);
+    const double rr = ctx->hst->red[1], bb = ctx->hst->red[2];
+    if (!(rr < bb)) {
+        *flags |= PISOC_FLAG_GUESS_FALLBACK;
+        O::guess_revert(ctx->L, s, ctx->ph, r, x, x64, b64, bsave, dg, ctx->part(PS_U));
+    }
+    return PISOC_OK;
+}
+
 template <typename T>
 pisoc_status one_step(pisoc_ctx* ctx, pisoc_step_info* info) {
     using O = Ops<T>;
@@ -392,6 +439,11 @@ pisoc_status one_step(pisoc_ctx* ctx, pisoc_step_info* info) {
                         cap ? snap + 2 * N : nullptr, f32 ? ctx->f<double>(Y.b64) : nullptr,
                         f32 ? ctx->f<double>(Y.x64a) : nullptr);
         });
+        if (p.guess == PISOC_GUESS_LEARNED) {
+            pisoc_status gs = learned_guess<T>(ctx, r, x, dg, w, p0, &flags);
+            if (gs != PISOC_OK) return gs;
+            if (flags & PISOC_FLAG_GUESS_FALLBACK) worst = std::max(worst, PISOC_WARN_GUESS_FALLBACK);
+        }
         int32_t it = 0, rounds = 0;
         double rel = 0.0;
         bool conv = false;
@@ -594,6 +646,8 @@ pisoc_status pisoc_init(const pisoc_params* prm, void* d_workspace, size_t ws_by
     };
     if (prm->precision == PISOC_FP64) convert(double{});
     else convert(float{});
+    if (prm->guess == PISOC_GUESS_LEARNED)
+        net_pack_forward(s, reinterpret_cast<const float*>(prm->d_guess_weights), ctx->ws + lay.wpk);
     if (sync_state(ctx) != PISOC_OK) return fail(PISOC_ERR_HIP);
     *out = ctx;
     return PISOC_OK;
@@ -834,6 +888,39 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
     (void)hipHostFree(ctx.hst);
     ctx.hst = nullptr;
     return st;
+}
+
+pisoc_status pisoc_net_inputs(int32_t n, const double* d_b, const double* d_diag,
+                              const double* d_p0, const double* d_psol, float* d_x, float* d_t,
+                              double* h_scales, void* d_workspace, size_t ws_bytes,
+                              void* hip_stream) {
+    if (n < PISOC_MIN_N || n > PISOC_MAX_N || !d_b || !d_diag || !d_p0 || !d_x ||
+        (d_t && !d_psol))
+        return PISOC_ERR_INVALID;
+    Layout lay = helm_layout(n);
+    if (!d_workspace || ws_bytes < lay.total ||
+        (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
+        return PISOC_ERR_WORKSPACE;
+    pisoc_params p{};
+    p.n = n;
+    p.gamma = 1.4;
+    p.C = 1.0;
+    Phys ph = make_phys(&p, 1.0);
+    Launch L = make_launch(n);
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    char* ws = reinterpret_cast<char*>(d_workspace);
+    DevState* st = reinterpret_cast<DevState*>(ws + lay.state);
+    double* part = reinterpret_cast<double*>(ws + lay.partials) + (size_t)PS_STAT * lay.max_blocks;
+    Ops<double>::net_stats(L, s, ph, d_b, d_diag, d_p0, part);
+    Ops<double>::net_input(L, s, ph, st, part, d_b, d_diag, d_p0, nullptr, d_x, d_psol, d_t);
+    if (hipGetLastError() != hipSuccess) return PISOC_ERR_HIP;
+    if (h_scales) {
+        if (hipMemcpyAsync(h_scales, &st->red[6], 2 * sizeof(double), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return PISOC_ERR_HIP;
+    }
+    return PISOC_OK;
 }
 
 }  // extern "C"

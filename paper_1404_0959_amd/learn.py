@@ -1,0 +1,111 @@
+"""Training and evaluation of the learned pressure-guess network.
+
+Data: the solver itself, run on seeded decaying-HIT cases (the 32^3, Mach
+0.2, Stokes 0.1, tolerance 1e-8 configuration), captures the pressure system
+of its first corrector after every step; the library turns each capture into
+the network's normalised inputs and target p'/s1.  Training: mini-batch Adam
+on the mean squared error with the project's own forward, backward and Adam
+kernels.  This module only orchestrates those calls (and holds the data
+tensors); every arithmetic step runs in the HIP library.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import pisoc as P
+from .inputs import make_hit_case
+
+
+def init_weights(seed: int = 0):
+    """He-normal initial weights, FP32 numpy vector of PISOC_NET_NWEIGHTS."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l in range(4):
+        cin, cout = P.NET_CH[l], P.NET_CH[l + 1]
+        std = math.sqrt(2.0 / (27 * cin)) if l < 3 else math.sqrt(1.0 / (27 * cin))
+        parts.append(rng.standard_normal(cout * cin * 27) * std)
+    return np.concatenate(parts).astype(np.float32)
+
+
+def generate(seeds, steps, n=32, mach=0.2, stokes=(0.1,), p_tol=1e-8, device="cuda:0", log=None):
+    """Snapshots (x [S, n^3, 2], t [S, n^3]) from the solver's first corrector."""
+    import torch
+    xs, ts = [], []
+    bits = P.FIELD_PSOLVE_B | P.FIELD_PSOLVE_DIAG | P.FIELD_P_PREV | P.FIELD_PSOLVE_X
+    for seed in seeds:
+        case = make_hit_case(n, seed, mach=mach, stokes=stokes)
+        s = P.Solver.from_case(case, p_tol=p_tol, capture=True, device=device)
+        for _ in range(steps):
+            st, _ = s.step(1)
+            if st < 0:
+                break
+            f = s.fields(bits)
+            x, t, _ = P.net_inputs(f[P.FIELD_PSOLVE_B], f[P.FIELD_PSOLVE_DIAG],
+                                   f[P.FIELD_P_PREV], f[P.FIELD_PSOLVE_X])
+            xs.append(x)
+            ts.append(t)
+        s.close()
+        if log:
+            log(f"seed {seed}: {len(xs)} snapshots")
+    return torch.stack(xs), torch.stack(ts)
+
+
+def train(x, t, epochs=20, batch=16, lr=2e-3, seed=0, w0=None, log=None):
+    """Adam on the MSE; returns (weights FP32 device tensor, loss history)."""
+    import torch
+    n = round(x.shape[1] ** (1 / 3))
+    dev = x.device
+    w = torch.as_tensor(init_weights(seed) if w0 is None else w0, device=dev).float().contiguous()
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    g = torch.empty_like(w)
+    net = P.Net(n, batch, device=dev)
+    rng = np.random.default_rng(seed + 1)
+    S = x.shape[0]
+    hist = []
+    step = 0
+    for ep in range(epochs):
+        perm = torch.as_tensor(rng.permutation(S), device=dev)
+        losses = []
+        for i in range(0, S - batch + 1, batch):
+            idx = perm[i:i + batch]
+            xb = x.index_select(0, idx).contiguous()
+            tb = t.index_select(0, idx).contiguous()
+            loss, _ = net.grad(w, xb, tb, out=g)
+            step += 1
+            net.adam(w, g, m, v, step, lr=lr)
+            losses.append(loss)
+        hist.append(float(np.mean(losses)))
+        if log:
+            log(f"epoch {ep}: loss {hist[-1]:.4e}")
+    return w, hist
+
+
+def evaluate(w, n, seeds, steps, mach=0.2, stokes=(0.2,), p_tol=1e-6, precision=P.FP64,
+             device="cuda:0"):
+    """CG iterations and wall time with and without the learned guess."""
+    import torch
+    out = {}
+    for name, kw in (("zero", {}), ("learned", dict(guess=P.GUESS_LEARNED,
+                                                   guess_weights=w.data_ptr()))):
+        its, fb, el = [], 0, 0.0
+        for seed in seeds:
+            case = make_hit_case(n, seed, mach=mach, stokes=stokes)
+            s = P.Solver.from_case(case, p_tol=p_tol, precision=precision, device=device, **kw)
+            s.step(1)                   # warm-up step (first-step prediction)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, info = s.step(steps)
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t0
+            for i in info:
+                its.append(sum(i["pcg_iters"]))
+                fb += 1 if i["flags"] & P.FLAG_GUESS_FALLBACK else 0
+                assert max(i["pcg_relres"]) <= p_tol
+            s.close()
+        out[name] = dict(iters_per_step=float(np.mean(its)), fallbacks=fb,
+                         ms_per_step=1e3 * el / (len(seeds) * steps))
+    return out

@@ -30,7 +30,11 @@ EXPORTED = [
     "pisoc_time", "pisoc_steps_done", "pisoc_destroy", "pisoc_last_error", "pisoc_status_string",
     "pisoc_helm_apply", "pisoc_helm_workspace_bytes", "pisoc_helm_solve",
     "pisoc_profile", "pisoc_profile_read",
+    "pisoc_net_workspace_bytes", "pisoc_net_forward", "pisoc_net_grad", "pisoc_net_adam",
+    "pisoc_net_inputs",
 ]
+NET_NWEIGHTS = 15120
+NET_CH = (2, 16, 16, 16, 1)
 
 MAX_KSTATS = 24
 
@@ -118,6 +122,18 @@ def lib():
     L.pisoc_profile.restype = C.c_int
     L.pisoc_profile_read.argtypes = [vp, C.POINTER(KernelStat), i32]
     L.pisoc_profile_read.restype = i32
+    fp = C.c_void_p
+    L.pisoc_net_workspace_bytes.argtypes = [i32, i32]
+    L.pisoc_net_workspace_bytes.restype = sz
+    L.pisoc_net_forward.argtypes = [i32, i32, fp, fp, fp, vp, sz, vp]
+    L.pisoc_net_forward.restype = C.c_int
+    L.pisoc_net_grad.argtypes = [i32, i32, fp, fp, fp, fp, C.POINTER(f64), vp, sz, vp]
+    L.pisoc_net_grad.restype = C.c_int
+    L.pisoc_net_adam.argtypes = [i32, fp, fp, fp, fp, i32, C.c_float, C.c_float, C.c_float,
+                                 C.c_float, vp]
+    L.pisoc_net_adam.restype = C.c_int
+    L.pisoc_net_inputs.argtypes = [i32, vp, vp, vp, vp, fp, fp, C.POINTER(f64), vp, sz, vp]
+    L.pisoc_net_inputs.restype = C.c_int
     _lib = L
     return L
 
@@ -274,6 +290,66 @@ class Solver:
         n = lib().pisoc_profile_read(self._h, arr, MAX_KSTATS)
         return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms,
                                            bytes=arr[i].bytes) for i in range(n)}
+
+
+class Net:
+    """Workspace-bound access to the network kernels for grids of n^3, batch b."""
+
+    def __init__(self, n, batch, device="cuda:0", stream=None):
+        torch = _torch()
+        self.torch, self.n, self.batch, self.stream = torch, n, batch, stream
+        nbytes = lib().pisoc_net_workspace_bytes(n, batch)
+        if nbytes == 0:
+            raise PisocError(ERR_INVALID, "network needs n % 16 == 0")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.nbytes = nbytes
+
+    def forward(self, w, x):
+        """x: FP32 [batch, n^3, 2] (device); returns FP32 [batch, n^3]."""
+        torch = self.torch
+        y = torch.empty(x.shape[0], self.n ** 3, dtype=torch.float32, device=x.device)
+        st = lib().pisoc_net_forward(self.n, x.shape[0], w.data_ptr(), x.data_ptr(), y.data_ptr(),
+                                     self.ws.data_ptr(), self.nbytes, _stream_ptr(torch, self.stream))
+        if st != OK:
+            raise PisocError(st, "pisoc_net_forward")
+        return y
+
+    def grad(self, w, x, t, out=None):
+        """(loss, FP32 gradient) of the mean squared error."""
+        torch = self.torch
+        g = out if out is not None else torch.empty_like(w)
+        loss = C.c_double(0.0)
+        st = lib().pisoc_net_grad(self.n, x.shape[0], w.data_ptr(), x.data_ptr(), t.data_ptr(),
+                                  g.data_ptr(), C.byref(loss), self.ws.data_ptr(), self.nbytes,
+                                  _stream_ptr(torch, self.stream))
+        if st != OK:
+            raise PisocError(st, "pisoc_net_grad")
+        return loss.value, g
+
+    def adam(self, w, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        st = lib().pisoc_net_adam(w.numel(), w.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                  step, lr, beta1, beta2, eps, _stream_ptr(self.torch, self.stream))
+        if st != OK:
+            raise PisocError(st, "pisoc_net_adam")
+
+
+def net_inputs(b, diag, p0, psol=None, stream=None):
+    """Network inputs (FP32 [n^3, 2]), optional target (FP32 [n^3]) and (s1, s2)
+    from one captured pressure system (FP64 device arrays)."""
+    torch = _torch()
+    n = b.shape[-1]
+    x = torch.empty(n ** 3, 2, dtype=torch.float32, device=b.device)
+    t = torch.empty(n ** 3, dtype=torch.float32, device=b.device) if psol is not None else None
+    nbytes = lib().pisoc_helm_workspace_bytes(n)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+    sc = (C.c_double * 2)()
+    st = lib().pisoc_net_inputs(n, b.data_ptr(), diag.data_ptr(), p0.data_ptr(),
+                                psol.data_ptr() if psol is not None else None, x.data_ptr(),
+                                t.data_ptr() if t is not None else None, sc, ws.data_ptr(), nbytes,
+                                _stream_ptr(torch, stream))
+    if st != OK:
+        raise PisocError(st, "pisoc_net_inputs")
+    return x, t, (sc[0], sc[1])
 
 
 def helm_apply(psidt, w, x, stream=None):
