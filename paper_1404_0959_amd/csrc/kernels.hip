@@ -624,20 +624,19 @@ __global__ void __launch_bounds__(kBlock) k_net_input(Phys ph, DevState* st, con
     END_CELLS
 }
 
-// Start CG from the network's guess x0 = s1 y: r = b - M x0 (difference form,
-// FP64 arithmetic), b kept in bsave for a fallback.  FP64 storage: x = x0.
-// FP32 storage (x64 non-null): the FP64 accumulator x64 = x0 and the inner
-// correction x = 0.  Partial sums r.(r/diag), ||r0||^2, ||b||^2.
+// The network's guess g = s1 y and M g (difference form, FP64 arithmetic),
+// stored in the CG scratch vectors, with partial sums g.b and g.(M g).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_guess_start(Phys ph, DevState* st,
+__global__ void __launch_bounds__(kBlock) k_guess_start(Phys ph, const DevState* st,
                                                         const float* __restrict__ y,
                                                         const T* __restrict__ w,
-                                                        const T* __restrict__ diag, T* __restrict__ r,
-                                                        T* __restrict__ x, double* __restrict__ x64,
+                                                        const T* __restrict__ diag,
+                                                        const T* __restrict__ b,
                                                         const double* __restrict__ b64,
-                                                        T* __restrict__ bsave, double* part_u) {
+                                                        T* __restrict__ gout, T* __restrict__ mg,
+                                                        double* part) {
     const double s1 = st->red[6], inv_h2 = ph.inv_h2;
-    double v[3] = {0.0, 0.0, 0.0};
+    double v[2] = {0.0, 0.0};
     FOR_CELLS(ph)
     auto g = [&](size_t Q) { return s1 * (double)y[Q]; };
     const double gP = g(P);
@@ -648,27 +647,57 @@ __global__ void __launch_bounds__(kBlock) k_guess_start(Phys ph, DevState* st,
         lap += kp * (gP - g(c.sh(d, 1))) + km * (gP - g(c.sh(d, -1)));
         sumK += kp + km;
     }
+    const double Mg = ((double)diag[P] - sumK * inv_h2) * gP + lap * inv_h2;
+    const double bP = b64 ? b64[P] : (double)b[P];
+    gout[P] = (T)gP;
+    mg[P] = (T)Mg;
+    v[0] += gP * bP;
+    v[1] += gP * Mg;
+    END_CELLS
+    block_partials<2, 0u>(v, part);
+}
+
+// Start CG from x0 = alpha g with the energy-optimal alpha = g.b / g.(M g) (the
+// first CG step along g, so that a poor guess is shrunk rather than followed):
+// r = b - alpha M g, b kept in bsave for a fallback.  FP64 storage: x = x0.
+// FP32 storage (x64 non-null): x64 = x0 and the inner correction x = 0.
+// Partial sums r.(r/diag), ||r0||^2, ||b||^2; alpha goes to st->red[5].
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_guess_apply(Phys ph, DevState* st, const double* part_g,
+                                                        unsigned nb, const T* __restrict__ g,
+                                                        const T* __restrict__ mg,
+                                                        const T* __restrict__ diag, T* __restrict__ r,
+                                                        T* __restrict__ x, double* __restrict__ x64,
+                                                        const double* __restrict__ b64,
+                                                        T* __restrict__ bsave, double* part_u) {
+    double t[2];
+    reduce_partials<2, 0u>(part_g, nb, t);
+    const double alpha = t[1] > 0.0 ? t[0] / t[1] : 0.0;
+    if (flat_bid() == 0 && flat_tid() == 0) {
+        st->red[5] = alpha;
+        st->pcg.it_stop = kIterInf;
+        st->pcg.converged = 0;
+        st->pcg.iters = 0;
+    }
+    double v[3] = {0.0, 0.0, 0.0};
+    FOR_CELLS(ph)
     const double bP = b64 ? b64[P] : (double)r[P];
-    const double r0 = bP - (((double)diag[P] - sumK * inv_h2) * gP + lap * inv_h2);
+    const double x0 = alpha * (double)g[P];
+    const double r0 = bP - alpha * (double)mg[P];
     bsave[P] = r[P];
     const T rT = (T)r0;
     r[P] = rT;
     if (x64) {
-        x64[P] = gP;
+        x64[P] = x0;
         x[P] = T(0);
     } else {
-        x[P] = (T)gP;
+        x[P] = (T)x0;
     }
     v[0] += (double)rT * ((double)rT / (double)diag[P]);
     v[1] += r0 * r0;
     v[2] += bP * bP;
     END_CELLS
     block_partials<3, 0u>(v, part_u);
-    if (flat_bid() == 0 && flat_tid() == 0) {
-        st->pcg.it_stop = kIterInf;
-        st->pcg.converged = 0;
-        st->pcg.iters = 0;
-    }
 }
 
 // Fallback to the zero guess: r = b, x = 0 (and x64 = 0), partials as corr_rhs.
@@ -1129,10 +1158,17 @@ void Ops<T>::net_input(const Launch& L, hipStream_t s, const Phys& ph, DevState*
     LAUNCH(k_net_input<T>, L, s, ph, st, part, L.nblocks, b, diag, p0, x4, x2, psol, tgt);
 }
 template <typename T>
-void Ops<T>::guess_start(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
-                         const float* y, const T* w, const T* diag, T* r, T* x, double* x64,
-                         const double* b64, T* bsave, double* part_u) {
-    LAUNCH(k_guess_start<T>, L, s, ph, st, y, w, diag, r, x, x64, b64, bsave, part_u);
+void Ops<T>::guess_start(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                         const float* y, const T* w, const T* diag, const T* b, const double* b64,
+                         T* g, T* mg, double* part) {
+    LAUNCH(k_guess_start<T>, L, s, ph, st, y, w, diag, b, b64, g, mg, part);
+}
+template <typename T>
+void Ops<T>::guess_apply(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
+                         const double* part_g, const T* g, const T* mg, const T* diag, T* r, T* x,
+                         double* x64, const double* b64, T* bsave, double* part_u) {
+    LAUNCH(k_guess_apply<T>, L, s, ph, st, part_g, L.nblocks, g, mg, diag, r, x, x64, b64, bsave,
+           part_u);
 }
 template <typename T>
 void Ops<T>::guess_revert(const Launch& L, hipStream_t s, const Phys& ph, T* r, T* x, double* x64,

@@ -352,9 +352,11 @@ pisoc_status refine_solve(pisoc_ctx* ctx, float* r, float* x, float* diag, float
 
 // The learned initial guess of one pressure solve: scaled inputs from the
 // system just set up, the network on the matrix cores, CG restarted from
-// x0 = s1 y; rejected (back to x0 = 0) unless ||b - M x0|| < ||b||.
+// x0 = alpha s1 y (alpha energy-optimal); rejected (back to x0 = 0) unless
+// ||b - M x0|| < ||b||.
 template <typename T>
-pisoc_status learned_guess(pisoc_ctx* ctx, T* r, T* x, T* dg, T* w, T* p0, int* flags) {
+pisoc_status learned_guess(pisoc_ctx* ctx, T* r, T* x, T* dg, T* w, T* p0, T* gbuf, T* mgbuf,
+                           int* flags) {
     using O = Ops<T>;
     const Layout& Y = ctx->lay;
     const bool f32 = sizeof(T) == sizeof(float);
@@ -368,8 +370,10 @@ pisoc_status learned_guess(pisoc_ctx* ctx, T* r, T* x, T* dg, T* w, T* p0, int* 
                      ctx->f<uint16_t>(Y.nx4), nullptr, nullptr, nullptr);
         net_forward(s, ctx->prm.n, 1, ctx->ws + Y.wpk, ctx->f<uint16_t>(Y.nx4),
                     ctx->f<uint16_t>(Y.na), ctx->f<uint16_t>(Y.nb), ctx->f<float>(Y.ny), 1.f);
-        O::guess_start(ctx->L, s, ctx->ph, ctx->st, ctx->f<float>(Y.ny), w, dg, r, x, x64, b64,
-                       bsave, ctx->part(PS_U));
+        O::guess_start(ctx->L, s, ctx->ph, ctx->st, ctx->f<float>(Y.ny), w, dg, r, b64, gbuf,
+                       mgbuf, ctx->part(PS_STAT));
+        O::guess_apply(ctx->L, s, ctx->ph, ctx->st, ctx->part(PS_STAT), gbuf, mgbuf, dg, r, x,
+                       x64, b64, bsave, ctx->part(PS_U));
     });
     // totals of r0.z0, ||r0||^2, ||b||^2 (3 columns written with L.nblocks blocks)
     const unsigned nb = ctx->L.nblocks;
@@ -440,7 +444,7 @@ pisoc_status one_step(pisoc_ctx* ctx, pisoc_step_info* info) {
                         f32 ? ctx->f<double>(Y.x64a) : nullptr);
         });
         if (p.guess == PISOC_GUESS_LEARNED) {
-            pisoc_status gs = learned_guess<T>(ctx, r, x, dg, w, p0, &flags);
+            pisoc_status gs = learned_guess<T>(ctx, r, x, dg, w, p0, pp0, q, &flags);
             if (gs != PISOC_OK) return gs;
             if (flags & PISOC_FLAG_GUESS_FALLBACK) worst = std::max(worst, PISOC_WARN_GUESS_FALLBACK);
         }

@@ -54,29 +54,42 @@ def generate(seeds, steps, n=32, mach=0.2, stokes=(0.1,), p_tol=1e-8, device="cu
 
 
 def train(x, t, epochs=20, batch=16, lr=2e-3, seed=0, w0=None, log=None):
-    """Adam on the MSE; returns (weights FP32 device tensor, loss history)."""
+    """Adam on the MSE; returns (weights FP32 device tensor, loss history).
+
+    x, t: one dataset (tensors [S, n^3, 2], [S, n^3]) or a list of datasets of
+    different grid sizes; mini-batches never mix sizes and each epoch visits
+    every batch of every size once, in a seeded random order."""
     import torch
-    n = round(x.shape[1] ** (1 / 3))
-    dev = x.device
+    sets = list(zip(x, t)) if isinstance(x, (list, tuple)) else [(x, t)]
+    dev = sets[0][0].device
     w = torch.as_tensor(init_weights(seed) if w0 is None else w0, device=dev).float().contiguous()
     m = torch.zeros_like(w)
     v = torch.zeros_like(w)
     g = torch.empty_like(w)
-    net = P.Net(n, batch, device=dev)
+    nets = []
+    for xs, _ in sets:
+        n = round(xs.shape[1] ** (1 / 3))
+        nets.append(P.Net(n, min(batch, xs.shape[0]), device=dev))
     rng = np.random.default_rng(seed + 1)
-    S = x.shape[0]
     hist = []
     step = 0
     for ep in range(epochs):
-        perm = torch.as_tensor(rng.permutation(S), device=dev)
+        jobs = []
+        for si, (xs, _) in enumerate(sets):
+            bsz = min(batch, xs.shape[0])
+            perm = rng.permutation(xs.shape[0])
+            jobs += [(si, perm[i:i + bsz]) for i in range(0, xs.shape[0] - bsz + 1, bsz)]
+        order = rng.permutation(len(jobs))
         losses = []
-        for i in range(0, S - batch + 1, batch):
-            idx = perm[i:i + batch]
-            xb = x.index_select(0, idx).contiguous()
-            tb = t.index_select(0, idx).contiguous()
-            loss, _ = net.grad(w, xb, tb, out=g)
+        for o in order:
+            si, idx = jobs[o]
+            xs, ts = sets[si]
+            ix = torch.as_tensor(idx, device=dev)
+            xb = xs.index_select(0, ix).contiguous()
+            tb = ts.index_select(0, ix).contiguous()
+            loss, _ = nets[si].grad(w, xb, tb, out=g)
             step += 1
-            net.adam(w, g, m, v, step, lr=lr)
+            nets[si].adam(w, g, m, v, step, lr=lr)
             losses.append(loss)
         hist.append(float(np.mean(losses)))
         if log:
