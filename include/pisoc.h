@@ -64,7 +64,7 @@ enum {
 /* initial value of each pressure solve */
 enum {
     PISOC_GUESS_ZERO = 0,   /* p' = 0 */
-    PISOC_GUESS_LEARNED = 1 /* 3D conv net prediction, with fallback to 0 */
+    PISOC_GUESS_LEARNED = 1 /* 3D conv net prediction; 0 where it does not lower ||r|| */
 };
 
 /* step-info flag bits */
@@ -185,6 +185,82 @@ typedef struct {
 pisoc_status pisoc_profile(pisoc_ctx* ctx, int32_t enable);
 /* Copies up to max entries (classes with launches > 0); returns the count. */
 int32_t pisoc_profile_read(const pisoc_ctx* ctx, pisoc_kernel_stat* h_out, int32_t max);
+
+/* ---- ensembles -------------------------------------------------------------
+ * Independent realisations stepped together: members of the same grid size form
+ * a size class whose kernels cover all its members in one launch (members
+ * stacked along z, each with its own dt, reference state, particle response
+ * times and pressure-solve state), and the classes run as parallel branches.
+ * Members may differ in n, C (hence the Mach number) and tau_p; every other
+ * parameter must be equal.  The ensemble creates and owns its HIP streams; the
+ * calls that step or read it synchronise them.
+ *
+ * PISOC_ENS_EAGER steps like pisoc_step, per class.  PISOC_ENS_GRAPH replays
+ * one captured HIP graph per step for the whole ensemble: each pressure solve
+ * runs a fixed number of CG iterations (sized from the iterations the members
+ * needed, +25% + 2) of which every launch after a member's own convergence
+ * returns at once, the FP32 refinement runs a fixed number of rounds, and the
+ * step is committed on the device.  The first captured call begins with one
+ * eager step that measures those iterations.  A solve that reaches its cap
+ * without converging flags PISOC_FLAG_PCG_MAXIT (status
+ * PISOC_WARN_NOT_CONVERGED, the state has advanced); the caps then grow and the
+ * graph is captured again on the next call.  A diverged member cannot be rolled
+ * back in this mode (PISOC_ERR_DIVERGED after the fact). */
+typedef struct pisoc_ens pisoc_ens;
+
+enum { PISOC_ENS_EAGER = 0, PISOC_ENS_GRAPH = 1 };
+
+typedef struct {
+    int32_t n, members;                 /* grid size, members of the class */
+    int32_t block_x, block_y, cells_z;  /* launch shape of the field kernels */
+    int32_t blocks;                     /* blocks per launch (all members) */
+    int32_t caps[PISOC_MAX_CORR];       /* captured step: CG iterations of each first solve */
+    int32_t cap_later;                  /* ... of each later refinement round */
+    int32_t rounds;                     /* ... FP64 refinement rounds (FP32_REFINED) */
+} pisoc_ens_class;
+
+/* Workspace for the ensemble (0 if the members are invalid); 256-byte aligned. */
+size_t pisoc_ens_workspace_bytes(const pisoc_params* h_members, int32_t count);
+
+/* As pisoc_init for `count` members: h_members[m] their parameters, and host
+ * arrays of device pointers d_rho[m], d_u[m], d_rho_p[m] (d_rho_p may be NULL
+ * without dust).  The set-up waits for work already on hip_stream. */
+pisoc_status pisoc_ens_init(const pisoc_params* h_members, int32_t count, void* d_workspace,
+                            size_t ws_bytes, const double* const* d_rho, const double* const* d_u,
+                            const double* const* d_rho_p, void* hip_stream, pisoc_ens** out);
+
+/* Advance every member n_steps steps (mode PISOC_ENS_EAGER or PISOC_ENS_GRAPH).
+ * h_info (host, may be NULL) receives `count` records: each member's last step,
+ * with flags accumulated over the call.  Synchronises. */
+pisoc_status pisoc_ens_step(pisoc_ens* ens, int32_t n_steps, int32_t mode, pisoc_step_info* h_info);
+
+/* As pisoc_fields for member m (asynchronous on the member's class stream;
+ * pisoc_ens_time or pisoc_ens_get_stats synchronise). */
+pisoc_status pisoc_ens_fields(pisoc_ens* ens, int32_t m, uint32_t which, double* const* d_dst);
+
+/* Statistics of every member into h_out[count]; synchronises. */
+pisoc_status pisoc_ens_get_stats(pisoc_ens* ens, pisoc_stats* h_out);
+
+/* Simulated time of every member into h_t[count]; synchronises. */
+pisoc_status pisoc_ens_time(pisoc_ens* ens, double* h_t);
+
+int64_t pisoc_ens_steps_done(const pisoc_ens* ens);
+int32_t pisoc_ens_num_classes(const pisoc_ens* ens);
+pisoc_status pisoc_ens_class_info(const pisoc_ens* ens, int32_t cls, pisoc_ens_class* h_out);
+
+/* Launch-shape autotuner: for every size class, times each candidate shape of
+ * the field kernels (block bx x 256/bx threads, cz cells per thread along z,
+ * at most 4096 blocks per member) on a representative set of the step's
+ * kernels -- a predictor sweep, H/A, the corrector set-up, two CG iterations
+ * and a dust sweep -- run on the systems of the last step, and keeps the
+ * fastest.  Winners are cached in the JSON file cache_path (may be NULL) under
+ * a key of grid size, members, precision, dust classes and guess; a cached
+ * entry is used without timing unless force != 0.  Needs one completed step.
+ * Synchronises; the captured graph is rebuilt on the next call. */
+pisoc_status pisoc_ens_autotune(pisoc_ens* ens, const char* cache_path, int32_t force);
+
+void pisoc_ens_destroy(pisoc_ens* ens);
+const char* pisoc_ens_last_error(const pisoc_ens* ens);
 
 /* ---- the pressure (Helmholtz) equation on its own -------------------------
  * The operator of each PISO corrector (Results section: PISO with fourth-order

@@ -16,29 +16,35 @@ constexpr int kMaxCorr = 4;
 constexpr int kMaxClasses = 8;
 constexpr int kIterInf = 0x7fffffff;
 
-// Constants of one grid and gas, passed by value to the kernels.
+// Constants of one grid size and gas, passed by value to the kernels.  A
+// launch covers `batch` members of the same size stacked along z (member m owns
+// the blocks with blockIdx.z in [m nz, (m+1) nz) and the cells [m N, (m+1) N) of
+// every field; vector components are NT = batch N apart).
 struct Phys {
     int n;
     int cz;             // cells per thread along z
+    int nz;             // blocks per member along z
+    int batch;          // members in the launch
+    size_t N, NT;       // cells per member, cells of all members
     double h, inv_h, inv_h2, V, inv_V, A;
     double gamma, C, mu;
-    double rho_ref, p_ref;  // reference state: rho and p are stored as deviations
 };
 
 // State of one pressure solve, kept on the device so that CG never returns to
 // the host between iterations.
 struct PcgState {
-    double bb;        // ||b||^2
+    double bb;        // reference ||b||^2 of the current solve
     double rzh[2];    // r.z of iterate k in slot k & 1
     double rr;        // ||r||^2 of the last checked iterate
-    double tol2;      // tol^2
+    double tol2;      // tol^2 of the current (inner) solve
+    double tol_final; // p_tol^2: the requested relative residual, squared
     int32_t it_stop;  // iteration index at which the solve stopped (kIterInf: running)
     int32_t maxit;
     int32_t iters;
     int32_t converged;
 };
 
-// Everything the host reads back after a batch of work.
+// Per-member device state, read back by the host after a batch of work.
 struct DevState {
     double dt, dt_prev, sigma, t;
     PcgState pcg;
@@ -49,26 +55,42 @@ struct DevState {
     double rho_min;
     double mass_p[kMaxClasses];
     double red[kMaxRed];
-    uint32_t counter[4];
+    // constants of the member: rho and p are stored as deviations from
+    // (rho_ref, p_ref); particle response times
+    double rho_ref, p_ref;
+    double tau[kMaxClasses];
+    double aff[2];     // per-member affine coefficients of a statistics pass
+    // record of the current step, per corrector
+    int32_t it_corr[kMaxCorr];     // CG iterations, all rounds
+    int32_t rounds_corr[kMaxCorr]; // FP64 refinement rounds
+    int32_t it_first[kMaxCorr];    // iterations of the first (fresh) solve
+    int32_t it_later[kMaxCorr];    // most iterations of one later refinement round
+    double rel_corr[kMaxCorr];     // final ||r|| / ||b||
+    // accumulated over the steps since the host last cleared them
+    int32_t flags_acc;
+    int32_t steps_acc;
+    int32_t it_first_max[kMaxCorr];
+    int32_t it_later_max[kMaxCorr];
 };
 
 // Geometry of a launch: blocks of 64x4 (or 32x8) threads over x-y, each
 // thread walking `cz` consecutive cells along z.
 struct CellIdx {
     int n, i, j, k;
+    size_t base;   // first cell of the member
     __device__ inline size_t at(int di, int dj, int dk) const {
         int a = i + di, b = j + dj, c = k + dk;
         a = a < 0 ? a + n : (a >= n ? a - n : a);
         b = b < 0 ? b + n : (b >= n ? b - n : b);
         c = c < 0 ? c + n : (c >= n ? c - n : c);
-        return (size_t)a + (size_t)n * ((size_t)b + (size_t)n * (size_t)c);
+        return base + (size_t)a + (size_t)n * ((size_t)b + (size_t)n * (size_t)c);
     }
     // cell reached by s steps along axis d
     __device__ inline size_t sh(int d, int s) const {
         return d == 0 ? at(s, 0, 0) : (d == 1 ? at(0, s, 0) : at(0, 0, s));
     }
     __device__ inline size_t self() const {
-        return (size_t)i + (size_t)n * ((size_t)j + (size_t)n * (size_t)k);
+        return base + (size_t)i + (size_t)n * ((size_t)j + (size_t)n * (size_t)k);
     }
 };
 
@@ -154,12 +176,10 @@ __device__ inline void block_partials(double (&v)[NV], double* part) {
     }
 }
 
-// Totals of partials written by an earlier kernel with `nb` blocks.  Every
-// block of the calling kernel computes the same totals in the same order
-// (bitwise identical, deterministic); all threads receive them.
+// Totals of count partials per column starting at `first`, columns nbt apart.
 template <int NV, unsigned MAXMASK>
-__device__ inline void reduce_partials(const double* __restrict__ part, unsigned nb,
-                                       double (&out)[NV]) {
+__device__ inline void reduce_partials_strided(const double* __restrict__ part, size_t nbt,
+                                               size_t first, unsigned nb, double (&out)[NV]) {
     __shared__ double lds[16 * NV];
     __shared__ double tot[NV];
     const int tid = flat_tid();
@@ -169,7 +189,7 @@ __device__ inline void reduce_partials(const double* __restrict__ part, unsigned
         const bool mx = (MAXMASK >> c) & 1u;
         double acc = mx ? -__builtin_inf() : 0.0;
         for (unsigned b = tid; b < nb; b += nthr) {
-            const double x = part[(size_t)c * nb + b];
+            const double x = part[(size_t)c * nbt + first + b];
             acc = mx ? (x > acc ? x : acc) : acc + x;
         }
         out[c] = acc;
@@ -183,6 +203,28 @@ __device__ inline void reduce_partials(const double* __restrict__ part, unsigned
     for (int c = 0; c < NV; ++c) out[c] = tot[c];
 }
 
+// Totals of one member's partials: an earlier kernel with nbt blocks in all
+// wrote column c of block b at part[c nbt + b]; member m owns the blocks
+// [m nbt/batch, (m+1) nbt/batch).
+template <int NV, unsigned MAXMASK>
+__device__ inline void reduce_member(const double* __restrict__ part, unsigned nbt, int batch,
+                                     int m, double (&out)[NV]) {
+    const unsigned per = nbt / (unsigned)batch;
+    double tmp[NV];
+    reduce_partials_strided<NV, MAXMASK>(part, nbt, (size_t)m * per, per, tmp);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) out[c] = tmp[c];
+}
+
+// Totals of partials written by an earlier kernel with `nb` blocks.  Every
+// block of the calling kernel computes the same totals in the same order
+// (bitwise identical, deterministic); all threads receive them.
+template <int NV, unsigned MAXMASK>
+__device__ inline void reduce_partials(const double* __restrict__ part, unsigned nb,
+                                       double (&out)[NV]) {
+    reduce_partials_strided<NV, MAXMASK>(part, nb, 0, nb, out);
+}
+
 // Round to nearest even FP32 -> BF16 (bit pattern); NaN stays NaN.
 __host__ __device__ inline uint16_t f2bf(float f) {
     uint32_t u = __builtin_bit_cast(uint32_t, f);
@@ -191,13 +233,13 @@ __host__ __device__ inline uint16_t f2bf(float f) {
     return (uint16_t)(u >> 16);
 }
 
-// Pressure deviation p(rho) - p_ref for rho = rho_ref + r, written with
-// log1p/expm1 so that it stays accurate for small r in FP32.
-__device__ inline double pdev(double r, const Phys& ph) {
-    return ph.p_ref * expm1(ph.gamma * log1p(r / ph.rho_ref));
+// Pressure deviation p(rho) - p_ref for rho = rho_ref + r (p_ref = C rho_ref^gamma),
+// written with log1p/expm1 so that it stays accurate for small r in FP32.
+__device__ inline double pdev(double r, double rho_ref, double p_ref, double gamma) {
+    return p_ref * expm1(gamma * log1p(r / rho_ref));
 }
-__device__ inline float pdev(float r, const Phys& ph) {
-    return (float)ph.p_ref * expm1f((float)ph.gamma * log1pf(r / (float)ph.rho_ref));
+__device__ inline float pdev(float r, double rho_ref, double p_ref, double gamma) {
+    return (float)p_ref * expm1f((float)gamma * log1pf(r / (float)rho_ref));
 }
 
 }  // namespace pisoc

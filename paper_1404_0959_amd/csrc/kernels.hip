@@ -12,17 +12,27 @@
 
 namespace pisoc {
 
+// The member of this block (blocks of member m have blockIdx.z in
+// [m nz, (m+1) nz)), its z-block and its first cell.
+#define MEMBER(ph)                                                           \
+    const int mem_ = (int)(blockIdx.z / (unsigned)(ph).nz);                  \
+    const int bz_ = (int)blockIdx.z - mem_ * (ph).nz;                        \
+    const size_t base_ = (size_t)mem_ * (ph).N;                              \
+    (void)bz_;                                                               \
+    (void)base_;
+// true in one thread of the member's first block
+#define MEMBER_FIRST() (blockIdx.x == 0 && blockIdx.y == 0 && bz_ == 0 && flat_tid() == 0)
 #define FOR_CELLS(ph)                                                        \
     const int ci_ = blockIdx.x * blockDim.x + threadIdx.x;                   \
     const int cj_ = blockIdx.y * blockDim.y + threadIdx.y;                   \
     for (int zz_ = 0; zz_ < (ph).cz; ++zz_) {                                \
-        const int ck_ = blockIdx.z * (ph).cz + zz_;                          \
+        const int ck_ = bz_ * (ph).cz + zz_;                                 \
         if (ci_ >= (ph).n || cj_ >= (ph).n || ck_ >= (ph).n) continue;       \
-        const CellIdx c{(ph).n, ci_, cj_, ck_};                              \
+        const CellIdx c{(ph).n, ci_, cj_, ck_, base_};                       \
         const size_t P = c.self();
 #define END_CELLS }
 
-__host__ __device__ static inline size_t ncell(const Phys& ph) { return (size_t)ph.n * ph.n * ph.n; }
+__host__ __device__ static inline size_t ncell(const Phys& ph) { return ph.NT; }
 
 // ---------------------------------------------------------------- utilities
 template <typename T>
@@ -41,21 +51,22 @@ __global__ void k_cast_out(const T* __restrict__ src, double* __restrict__ dst, 
     for (; i < count; i += stride) dst[i] = (double)src[i] + shift;
 }
 
-// p = p_ref + p_dev(r) as FP64
+// p = p_ref + p_dev(r) as FP64 (one member)
 template <typename T>
-__global__ void k_pressure_out(Phys ph, const T* __restrict__ r, double* __restrict__ dst,
-                               size_t count) {
+__global__ void k_pressure_out(double gamma, double rho_ref, double p_ref, const T* __restrict__ r,
+                               double* __restrict__ dst, size_t count) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < count; i += stride) dst[i] = ph.p_ref + pdev((double)r[i], ph);
+    for (; i < count; i += stride) dst[i] = p_ref + pdev((double)r[i], rho_ref, p_ref, gamma);
 }
 
 // Initial face mass fluxes phi_d = I4(rho) I4(u_d) A.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_init_phi(Phys ph, const T* __restrict__ r,
+__global__ void __launch_bounds__(kBlock) k_init_phi(Phys ph, const DevState* st, const T* __restrict__ r,
                                                      const T* __restrict__ u, T* __restrict__ phi) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
-    const T rref = (T)ph.rho_ref, A = (T)ph.A;
+    const T rref = (T)(st + mem_)->rho_ref, A = (T)ph.A;
     FOR_CELLS(ph)
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -67,8 +78,9 @@ __global__ void __launch_bounds__(kBlock) k_init_phi(Phys ph, const T* __restric
 // Per-block maxima of the convective Courant rate
 // sigma_P = sum_f |phi_f| / (2 rho_P V); the next kernel turns them into dt.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_cfl(Phys ph, const T* __restrict__ r,
+__global__ void __launch_bounds__(kBlock) k_cfl(Phys ph, const DevState* st, const T* __restrict__ r,
                                                 const T* __restrict__ phi, double* part) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
     double v[1] = {0.0};
     FOR_CELLS(ph)
@@ -76,7 +88,7 @@ __global__ void __launch_bounds__(kBlock) k_cfl(Phys ph, const T* __restrict__ r
 #pragma unroll
     for (int d = 0; d < 3; ++d)
         f += fabs((double)phi[d * N + P]) + fabs((double)phi[d * N + c.sh(d, -1)]);
-    double s = f / (2.0 * (ph.rho_ref + (double)r[P]) * ph.V);
+    double s = f / (2.0 * ((st + mem_)->rho_ref + (double)r[P]) * ph.V);
     v[0] = s > v[0] ? s : v[0];
     END_CELLS
     block_partials<1, 1u>(v, part);
@@ -89,14 +101,16 @@ __global__ void __launch_bounds__(kBlock) k_cfl(Phys ph, const T* __restrict__ r
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_predict(Phys ph, DevState* st, const double* part_cfl,
                                                     unsigned nb, double dt_fixed, double cfl,
-                                                    double growth, double dt_prev, double dt_max,
+                                                    double growth, double dt_max,
                                                     const T* __restrict__ rn, const T* __restrict__ un,
                                                     const T* __restrict__ phi, T* __restrict__ rs,
                                                     T* __restrict__ aP, T* __restrict__ divu,
                                                     T* __restrict__ pn) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
     double sg[1];
-    reduce_partials<1, 1u>(part_cfl, nb, sg);
+    reduce_member<1, 1u>(part_cfl, nb, ph.batch, mem_, sg);
+    const double dt_prev = (st + mem_)->dt_prev;
     double dtd;
     if (dt_fixed > 0.0) {
         dtd = dt_fixed;
@@ -105,10 +119,10 @@ __global__ void __launch_bounds__(kBlock) k_predict(Phys ph, DevState* st, const
         if (growth * dt_prev < dtd) dtd = growth * dt_prev;
         if (dt_max > 0.0 && dt_max < dtd) dtd = dt_max;
     }
-    if (flat_bid() == 0 && flat_tid() == 0) {
-        if (!(dtd > 0.0) || !isfinite(dtd)) st->flags |= 16;  // bad dt
-        st->sigma = sg[0];
-        st->dt = dtd;
+    if (MEMBER_FIRST()) {
+        if (!(dtd > 0.0) || !isfinite(dtd)) (st + mem_)->flags |= 16;  // bad dt
+        (st + mem_)->sigma = sg[0];
+        (st + mem_)->dt = dtd;
     }
     const T dt = (T)dtd;
     const T inv_V = (T)ph.inv_V, inv_h = (T)ph.inv_h;
@@ -120,12 +134,12 @@ __global__ void __launch_bounds__(kBlock) k_predict(Phys ph, DevState* st, const
     dphi *= inv_V;
     T r = rn[P] - dt * dphi;
     rs[P] = r;
-    aP[P] = ((T)ph.rho_ref + r) / dt + T(0.5625) * dphi + diag_visc;
+    aP[P] = ((T)(st + mem_)->rho_ref + r) / dt + T(0.5625) * dphi + diag_visc;
     T du = T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) du += i4(un + d * N, c, d, 0) - i4(un + d * N, c, d, -1);
     divu[P] = du * inv_h;
-    pn[P] = pdev(rn[P], ph);
+    pn[P] = pdev(rn[P], (st + mem_)->rho_ref, (st + mem_)->p_ref, ph.gamma);
     END_CELLS
 }
 
@@ -136,11 +150,12 @@ __global__ void __launch_bounds__(kBlock) k_mom_source(Phys ph, const DevState* 
                                                        const T* __restrict__ un,
                                                        const T* __restrict__ divu,
                                                        T* __restrict__ s) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
-    const T dt = (T)st->dt;
+    const T dt = (T)(st + mem_)->dt;
     const T m3 = (T)(ph.mu / 3.0), inv_h = (T)ph.inv_h;
     FOR_CELLS(ph)
-    const T rho = (T)ph.rho_ref + rn[P];
+    const T rho = (T)(st + mem_)->rho_ref + rn[P];
 #pragma unroll
     for (int m = 0; m < 3; ++m) s[m * N + P] = rho * un[m * N + P] / dt + m3 * dgauss(divu, c, m, inv_h);
     END_CELLS
@@ -152,11 +167,12 @@ __global__ void __launch_bounds__(kBlock) k_mom_source(Phys ph, const DevState* 
 // stores w = rho_k / a_P and p_dev(rho_k) of the current density iterate.
 // N(u) = (1/V) sum_f phi_f^out I4(u)_f - (9/16) div(phi) u_P - mu sum_nb u_nb / h^2.
 template <typename T, bool HBYA>
-__global__ void __launch_bounds__(kBlock) k_mom_sweep(Phys ph, const T* __restrict__ uin,
+__global__ void __launch_bounds__(kBlock) k_mom_sweep(Phys ph, const DevState* st, const T* __restrict__ uin,
                                                       T* __restrict__ uout, const T* __restrict__ phi,
                                                       const T* __restrict__ aP, const T* __restrict__ s,
                                                       const T* __restrict__ pn, const T* __restrict__ rk,
                                                       T* __restrict__ w, T* __restrict__ p0) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
     const T inv_V = (T)ph.inv_V, inv_h = (T)ph.inv_h;
     const T mu_h2 = (T)(ph.mu * ph.inv_h2);
@@ -186,8 +202,8 @@ __global__ void __launch_bounds__(kBlock) k_mom_sweep(Phys ph, const T* __restri
         uout[m * N + P] = rhs / a;
     }
     if (HBYA) {
-        w[P] = ((T)ph.rho_ref + rk[P]) / a;
-        p0[P] = pdev(rk[P], ph);
+        w[P] = ((T)(st + mem_)->rho_ref + rk[P]) / a;
+        p0[P] = pdev(rk[P], (st + mem_)->rho_ref, (st + mem_)->p_ref, ph.gamma);
     }
     END_CELLS
 }
@@ -207,10 +223,11 @@ __global__ void __launch_bounds__(kBlock) k_corr_rhs(
     T* __restrict__ phiH, T* __restrict__ rvec, T* __restrict__ x, T* __restrict__ diag,
     double* part_u, double* snap_b, double* snap_diag, double* snap_p0, double* b64,
     double* x64) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
-    const double dt = st->dt;
+    const double dt = (st + mem_)->dt;
     const double A = ph.A, inv_V = ph.inv_V, inv_h = ph.inv_h, inv_h2 = ph.inv_h2;
-    const double rref = ph.rho_ref;
+    const double rref = (st + mem_)->rho_ref;
     double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
     double divF = 0.0, sumK = 0.0;
@@ -231,7 +248,7 @@ __global__ void __launch_bounds__(kBlock) k_corr_rhs(
     }
     const double b = -(((double)rk[P] - (double)rn[P]) / dt + divF * inv_V);
     const double rho = rref + (double)rk[P];
-    const double psidt = rho / (ph.gamma * (ph.p_ref + p0P)) / dt;
+    const double psidt = rho / (ph.gamma * ((st + mem_)->p_ref + p0P)) / dt;
     const T dgT = (T)(psidt + sumK * inv_h2);
     const T bT = (T)b;
     rvec[P] = bT;
@@ -248,14 +265,14 @@ __global__ void __launch_bounds__(kBlock) k_corr_rhs(
     if (snap_b) {
         snap_b[P] = b;
         snap_diag[P] = (double)dgT;
-        snap_p0[P] = ph.p_ref + p0P;
+        snap_p0[P] = (st + mem_)->p_ref + p0P;
     }
     END_CELLS
     block_partials<3, 0u>(v, part_u);
-    if (flat_bid() == 0 && flat_tid() == 0) {
-        st->pcg.it_stop = kIterInf;
-        st->pcg.converged = 0;
-        st->pcg.iters = 0;
+    if (MEMBER_FIRST()) {
+        (st + mem_)->pcg.it_stop = kIterInf;
+        (st + mem_)->pcg.converged = 0;
+        (st + mem_)->pcg.iters = 0;
     }
 }
 
@@ -271,6 +288,7 @@ __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
                                                    const double* __restrict__ b64,
                                                    const T* __restrict__ w, const T* __restrict__ diag,
                                                    T* __restrict__ r32, double* part_u) {
+    MEMBER(ph)
     const double inv_h2 = ph.inv_h2;
     double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
@@ -292,10 +310,10 @@ __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
     v[2] += r * r;
     END_CELLS
     block_partials<3, 0u>(v, part_u);
-    if (flat_bid() == 0 && flat_tid() == 0) {
-        st->pcg.it_stop = kIterInf;
-        st->pcg.converged = 0;
-        st->pcg.iters = 0;
+    if (MEMBER_FIRST()) {
+        (st + mem_)->pcg.it_stop = kIterInf;
+        (st + mem_)->pcg.converged = 0;
+        (st + mem_)->pcg.iters = 0;
     }
 }
 
@@ -321,27 +339,33 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(Phys ph, DevState* st, int 
                                                      const T* __restrict__ w, const T* __restrict__ pold,
                                                      T* __restrict__ pnew, T* __restrict__ q,
                                                      const double* part_u, double* part_s, unsigned nb,
-                                                     double tol2, int maxit) {
-    if (k >= st->pcg.it_stop) return;
+                                                     int fresh, int maxit) {
+    MEMBER(ph)
+    if (k >= (st + mem_)->pcg.it_stop) return;
     double t[3];
-    reduce_partials<3, 0u>(part_u, nb, t);
+    reduce_member<3, 0u>(part_u, nb, ph.batch, mem_, t);
     const double rz = t[0], rr = t[1];
-    const double bb = k == 0 ? t[2] : st->pcg.bb;
+    // reference ||b||^2: from this system's partials on the first iteration of
+    // a fresh solve, else the stored one (later refinement rounds measure
+    // against the original right-hand side); tolerance from the member state
+    const bool newb = fresh && k == 0;
+    const double bb = newb ? t[2] : (st + mem_)->pcg.bb;
+    const double tol2 = (st + mem_)->pcg.tol2;
     const bool conv = rr <= tol2 * bb;
     const bool stop = conv || k >= maxit;
-    if (flat_bid() == 0 && flat_tid() == 0) {
-        PcgState& g = st->pcg;
+    if (MEMBER_FIRST()) {
+        PcgState& g = (st + mem_)->pcg;
         g.rr = rr;
         g.iters = k;
         g.rzh[k & 1] = rz;
-        if (k == 0) g.bb = bb;
+        if (newb) g.bb = bb;
         if (stop) {
             g.it_stop = k;
             g.converged = conv ? 1 : 0;
         }
     }
     if (stop) return;
-    const T beta = k == 0 ? T(0) : (T)(rz / st->pcg.rzh[(k - 1) & 1]);
+    const T beta = k == 0 ? T(0) : (T)(rz / (st + mem_)->pcg.rzh[(k - 1) & 1]);
     const bool first = k == 0;
     const T inv_h2 = (T)ph.inv_h2;
     double v[1] = {0.0};
@@ -377,33 +401,39 @@ template <typename T>
 __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     Phys ph, DevState* st, int k, const T* __restrict__ r, const T* __restrict__ diag,
     const T* __restrict__ w, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ q,
-    const double* part_u, unsigned nb_u, double* part_s, double tol2, int maxit) {
-    if (k >= st->pcg.it_stop) return;
+    const double* part_u, unsigned nb_u, double* part_s, int fresh, int maxit) {
+    MEMBER(ph)
+    if (k >= (st + mem_)->pcg.it_stop) return;
     double t[3];
-    reduce_partials<3, 0u>(part_u, nb_u, t);
+    reduce_member<3, 0u>(part_u, nb_u, ph.batch, mem_, t);
     const double rz = t[0], rr = t[1];
-    const double bb = k == 0 ? t[2] : st->pcg.bb;
+    // reference ||b||^2: from this system's partials on the first iteration of
+    // a fresh solve, else the stored one (later refinement rounds measure
+    // against the original right-hand side); tolerance from the member state
+    const bool newb = fresh && k == 0;
+    const double bb = newb ? t[2] : (st + mem_)->pcg.bb;
+    const double tol2 = (st + mem_)->pcg.tol2;
     const bool conv = rr <= tol2 * bb;
     const bool stop = conv || k >= maxit;
-    if (flat_bid() == 0 && flat_tid() == 0) {
-        PcgState& g = st->pcg;
+    if (MEMBER_FIRST()) {
+        PcgState& g = (st + mem_)->pcg;
         g.rr = rr;
         g.iters = k;
         g.rzh[k & 1] = rz;
-        if (k == 0) g.bb = bb;
+        if (newb) g.bb = bb;
         if (stop) {
             g.it_stop = k;
             g.converged = conv ? 1 : 0;
         }
     }
     if (stop) return;
-    const T beta = k == 0 ? T(0) : (T)(rz / st->pcg.rzh[(k - 1) & 1]);
+    const T beta = k == 0 ? T(0) : (T)(rz / (st + mem_)->pcg.rzh[(k - 1) & 1]);
     const bool first = k == 0;
     const T inv_h2 = (T)ph.inv_h2;
     const int n = ph.n, cz = ph.cz;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kTX * ty;
     const int i0 = blockIdx.x * kTX, j0 = blockIdx.y * kTY;
-    const int k0 = blockIdx.z * cz;
+    const int k0 = bz_ * cz;
     const int k1 = k0 + cz < n ? k0 + cz : n;
     const size_t nn = (size_t)n * n;
     __shared__ T ws[kTY + 4][kTX + 4];
@@ -413,7 +443,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
         const T zz = r[Q] / diag[Q];
         return first ? zz : zz + beta * pold[Q];
     };
-    const size_t col = (size_t)(i0 + tx) + (size_t)n * (j0 + ty);
+    const size_t col = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty);
     T wq0 = w[col + nn * wr(k0 - 2)], wq1 = w[col + nn * wr(k0 - 1)], wq2 = w[col + nn * k0],
       wq3 = w[col + nn * wr(k0 + 1)];
     T pm = dirv(col + nn * wr(k0 - 1)), pc = dirv(col + nn * k0);
@@ -425,25 +455,25 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
         const int row = tid >> 6, x = tid & 63;
         hy = row < 2 ? row : kTY + row;
         hx = x + 2;
-        hoff = (size_t)(i0 + x) + (size_t)n * wr(j0 - 2 + hy);
+        hoff = base_ + (size_t)(i0 + x) + (size_t)n * wr(j0 - 2 + hy);
         hkind = 1;
     } else if (tid < 288) {     // w columns i0-2, i0-1, i0+64, i0+65
         const int t2 = tid - 256, c4 = t2 >> 3, y = t2 & 7;
         hx = c4 < 2 ? c4 : kTX + c4;
         hy = y + 2;
-        hoff = (size_t)wr(i0 - 2 + hx) + (size_t)n * (j0 + y);
+        hoff = base_ + (size_t)wr(i0 - 2 + hx) + (size_t)n * (j0 + y);
         hkind = 1;
     } else if (tid < 416) {     // p rows j0-1, j0+8
         const int t3 = tid - 288, row = t3 >> 6, x = t3 & 63;
         hy = row == 0 ? 0 : kTY + 1;
         hx = x + 1;
-        hoff = (size_t)(i0 + x) + (size_t)n * wr(j0 - 1 + hy);
+        hoff = base_ + (size_t)(i0 + x) + (size_t)n * wr(j0 - 1 + hy);
         hkind = 2;
     } else if (tid < 432) {     // p columns i0-1, i0+64
         const int t4 = tid - 416, c2 = t4 >> 3, y = t4 & 7;
         hx = c2 == 0 ? 0 : kTX + 1;
         hy = y + 1;
-        hoff = (size_t)wr(i0 - 1 + hx) + (size_t)n * (j0 + y);
+        hoff = base_ + (size_t)wr(i0 - 1 + hx) + (size_t)n * (j0 + y);
         hkind = 2;
     }
     double acc = 0.0;
@@ -498,10 +528,11 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(Phys ph, const DevState* 
                                                        const T* __restrict__ diag, T* __restrict__ x,
                                                        const T* __restrict__ p, const double* part_s,
                                                        double* part_u, unsigned nb_s) {
-    if (k >= st->pcg.it_stop) return;
+    MEMBER(ph)
+    if (k >= (st + mem_)->pcg.it_stop) return;
     double pq[1];
-    reduce_partials<1, 0u>(part_s, nb_s, pq);
-    const T alpha = (T)(st->pcg.rzh[k & 1] / pq[0]);
+    reduce_member<1, 0u>(part_s, nb_s, ph.batch, mem_, pq);
+    const T alpha = (T)((st + mem_)->pcg.rzh[k & 1] / pq[0]);
     double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
     x[P] += alpha * p[P];
@@ -518,6 +549,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_helm_apply(Phys ph, const T* __restrict__ psidt,
                                                        const T* __restrict__ w, const T* __restrict__ x,
                                                        T* __restrict__ y) {
+    MEMBER(ph)
     const T inv_h2 = (T)ph.inv_h2;
     FOR_CELLS(ph)
     const T xP = x[P];
@@ -539,6 +571,7 @@ __global__ void __launch_bounds__(kBlock) k_helm_start(Phys ph, DevState* st,
                                                        const T* __restrict__ w, const T* __restrict__ b,
                                                        const T* __restrict__ x, T* __restrict__ r,
                                                        T* __restrict__ diag, double* part_u) {
+    MEMBER(ph)
     const T inv_h2 = (T)ph.inv_h2;
     double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
@@ -559,10 +592,10 @@ __global__ void __launch_bounds__(kBlock) k_helm_start(Phys ph, DevState* st,
     v[2] += (double)b[P] * (double)b[P];
     END_CELLS
     block_partials<3, 0u>(v, part_u);
-    if (flat_bid() == 0 && flat_tid() == 0) {
-        st->pcg.it_stop = kIterInf;
-        st->pcg.converged = 0;
-        st->pcg.iters = 0;
+    if (MEMBER_FIRST()) {
+        (st + mem_)->pcg.it_stop = kIterInf;
+        (st + mem_)->pcg.converged = 0;
+        (st + mem_)->pcg.iters = 0;
     }
 }
 
@@ -572,6 +605,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_net_stats(Phys ph, const T* __restrict__ b,
                                                       const T* __restrict__ diag,
                                                       const T* __restrict__ p0, double* part) {
+    MEMBER(ph)
     double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
     const double z = (double)b[P] / (double)diag[P];
@@ -586,7 +620,7 @@ __global__ void __launch_bounds__(kBlock) k_net_stats(Phys ph, const T* __restri
 // Network inputs: channel 0 = (b/diag)/s1, channel 1 = (p0 - <p0>)/s2 with s1, s2
 // their r.m.s. (the Jacobi-scaled continuity defect and the pressure of the
 // current density iterate, each normalised); BF16 [cell][4] and/or FP32
-// [cell][2]; with psol the training target psol/s1.  s1, s2 go to st->red[6..7].
+// [cell][2]; with psol the training target psol/s1.  s1, s2 go to (st + mem_)->red[6..7].
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_net_input(Phys ph, DevState* st, const double* part,
                                                       unsigned nb, const T* __restrict__ b,
@@ -595,17 +629,18 @@ __global__ void __launch_bounds__(kBlock) k_net_input(Phys ph, DevState* st, con
                                                       uint16_t* __restrict__ x4, float* __restrict__ x2,
                                                       const T* __restrict__ psol,
                                                       float* __restrict__ tgt) {
+    MEMBER(ph)
     double t[3];
-    reduce_partials<3, 0u>(part, nb, t);
-    const double N = (double)ncell(ph);
+    reduce_member<3, 0u>(part, nb, ph.batch, mem_, t);
+    const double N = (double)ph.N;
     const double s1 = sqrt(t[0] / N);
     const double mean = t[1] / N;
     const double var = t[2] / N - mean * mean;
     const double s2 = var > 0.0 ? sqrt(var) : 0.0;
     const double i1 = s1 > 0.0 ? 1.0 / s1 : 0.0, i2 = s2 > 0.0 ? 1.0 / s2 : 0.0;
-    if (st && flat_bid() == 0 && flat_tid() == 0) {
-        st->red[6] = s1;
-        st->red[7] = s2;
+    if (st && MEMBER_FIRST()) {
+        (st + mem_)->red[6] = s1;
+        (st + mem_)->red[7] = s2;
     }
     FOR_CELLS(ph)
     const float c0 = (float)((double)b[P] / (double)diag[P] * i1);
@@ -635,7 +670,8 @@ __global__ void __launch_bounds__(kBlock) k_guess_start(Phys ph, const DevState*
                                                         const double* __restrict__ b64,
                                                         T* __restrict__ gout, T* __restrict__ mg,
                                                         double* part) {
-    const double s1 = st->red[6], inv_h2 = ph.inv_h2;
+    MEMBER(ph)
+    const double s1 = (st + mem_)->red[6], inv_h2 = ph.inv_h2;
     double v[2] = {0.0, 0.0};
     FOR_CELLS(ph)
     auto g = [&](size_t Q) { return s1 * (double)y[Q]; };
@@ -661,7 +697,7 @@ __global__ void __launch_bounds__(kBlock) k_guess_start(Phys ph, const DevState*
 // first CG step along g, so that a poor guess is shrunk rather than followed):
 // r = b - alpha M g, b kept in bsave for a fallback.  FP64 storage: x = x0.
 // FP32 storage (x64 non-null): x64 = x0 and the inner correction x = 0.
-// Partial sums r.(r/diag), ||r0||^2, ||b||^2; alpha goes to st->red[5].
+// Partial sums r.(r/diag), ||r0||^2, ||b||^2; alpha goes to (st + mem_)->red[5].
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_guess_apply(Phys ph, DevState* st, const double* part_g,
                                                         unsigned nb, const T* __restrict__ g,
@@ -670,14 +706,15 @@ __global__ void __launch_bounds__(kBlock) k_guess_apply(Phys ph, DevState* st, c
                                                         T* __restrict__ x, double* __restrict__ x64,
                                                         const double* __restrict__ b64,
                                                         T* __restrict__ bsave, double* part_u) {
+    MEMBER(ph)
     double t[2];
-    reduce_partials<2, 0u>(part_g, nb, t);
+    reduce_member<2, 0u>(part_g, nb, ph.batch, mem_, t);
     const double alpha = t[1] > 0.0 ? t[0] / t[1] : 0.0;
-    if (flat_bid() == 0 && flat_tid() == 0) {
-        st->red[5] = alpha;
-        st->pcg.it_stop = kIterInf;
-        st->pcg.converged = 0;
-        st->pcg.iters = 0;
+    if (MEMBER_FIRST()) {
+        (st + mem_)->red[5] = alpha;
+        (st + mem_)->pcg.it_stop = kIterInf;
+        (st + mem_)->pcg.converged = 0;
+        (st + mem_)->pcg.iters = 0;
     }
     double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
@@ -700,13 +737,19 @@ __global__ void __launch_bounds__(kBlock) k_guess_apply(Phys ph, DevState* st, c
     block_partials<3, 0u>(v, part_u);
 }
 
-// Fallback to the zero guess: r = b, x = 0 (and x64 = 0), partials as corr_rhs.
+// Fallback to the zero guess where the guess does not lower the residual
+// (red[1] = ||b - M x0||^2 not below red[2] = ||b||^2, totals left by
+// finalize_sums): r = b, x = 0 (and x64 = 0), partials as corr_rhs, flag 8.
+// The decision is per member, so all blocks of a member agree.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_guess_revert(Phys ph, T* __restrict__ r,
+__global__ void __launch_bounds__(kBlock) k_guess_revert(Phys ph, DevState* st, T* __restrict__ r,
                                                          T* __restrict__ x, double* __restrict__ x64,
                                                          const double* __restrict__ b64,
                                                          const T* __restrict__ bsave,
                                                          const T* __restrict__ diag, double* part_u) {
+    MEMBER(ph)
+    if ((st + mem_)->red[1] < (st + mem_)->red[2]) return;
+    if (MEMBER_FIRST()) (st + mem_)->flags |= 8;
     double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
     const T bT = bsave[P];
@@ -728,6 +771,7 @@ __global__ void __launch_bounds__(kBlock) k_corr_flux(Phys ph, const T* __restri
                                                       const T* __restrict__ x, const T* __restrict__ w,
                                                       const T* __restrict__ phiH, T* __restrict__ phik,
                                                       T* __restrict__ pt, double* snap_x) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
     const T A = (T)ph.A, inv_h = (T)ph.inv_h;
     FOR_CELLS(ph)
@@ -754,8 +798,9 @@ __global__ void __launch_bounds__(kBlock) k_corr_update(Phys ph, const DevState*
                                                         const T* __restrict__ pt,
                                                         const T* __restrict__ aP, T* __restrict__ rk,
                                                         T* __restrict__ u, double* partials) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
-    const T dt = (T)st->dt;
+    const T dt = (T)(st + mem_)->dt;
     const T inv_V = (T)ph.inv_V, inv_h = (T)ph.inv_h;
     double v[3] = {0.0, 0.0, -__builtin_inf()};
     FOR_CELLS(ph)
@@ -775,7 +820,7 @@ __global__ void __launch_bounds__(kBlock) k_corr_update(Phys ph, const DevState*
     if (LAST) {
         v[0] += (double)r;
         v[1] += usq;
-        double nrho = -(ph.rho_ref + (double)r);
+        double nrho = -((st + mem_)->rho_ref + (double)r);
         v[2] = nrho > v[2] ? nrho : v[2];
     }
     END_CELLS
@@ -788,8 +833,9 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dudt(Phys ph, const DevState* st,
                                                  const T* __restrict__ un, const T* __restrict__ u1,
                                                  T* __restrict__ acc) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
-    const T dt = (T)st->dt, inv_h = (T)ph.inv_h;
+    const T dt = (T)(st + mem_)->dt, inv_h = (T)ph.inv_h;
     FOR_CELLS(ph)
     const T ux = u1[P], uy = u1[N + P], uz = u1[2 * N + P];
 #pragma unroll
@@ -806,12 +852,13 @@ __global__ void __launch_bounds__(kBlock) k_dudt(Phys ph, const DevState* st,
 // G_d = phi_d - tau I4(rho^{n+1}) I4(a_d) A  (u_p = u - tau Du/Dt at the face),
 // and the starting mass ratio Y = rho_j^n / rho^n.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_dust_flux(Phys ph, double tau, const T* __restrict__ phi,
+__global__ void __launch_bounds__(kBlock) k_dust_flux(Phys ph, const DevState* st, int cls, const T* __restrict__ phi,
                                                       const T* __restrict__ r1, const T* __restrict__ acc,
                                                       T* __restrict__ G, const T* __restrict__ rhoj,
                                                       const T* __restrict__ rn, T* __restrict__ Y) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
-    const T A = (T)ph.A, t = (T)tau, rref = (T)ph.rho_ref;
+    const T A = (T)ph.A, t = (T)(st + mem_)->tau[cls], rref = (T)(st + mem_)->rho_ref;
     FOR_CELLS(ph)
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -828,8 +875,9 @@ __global__ void __launch_bounds__(kBlock) k_dust_sweep(Phys ph, const DevState* 
                                                        const T* __restrict__ Yin, T* __restrict__ Yout,
                                                        const T* __restrict__ G, const T* __restrict__ rhoj,
                                                        const T* __restrict__ r1) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
-    const T dt = (T)st->dt, inv_V = (T)ph.inv_V;
+    const T dt = (T)(st + mem_)->dt, inv_V = (T)ph.inv_V;
     FOR_CELLS(ph)
     T conv = T(0), dG = T(0);
 #pragma unroll
@@ -841,7 +889,7 @@ __global__ void __launch_bounds__(kBlock) k_dust_sweep(Phys ph, const DevState* 
     conv *= inv_V;
     dG *= inv_V;
     const T off = conv - T(0.5625) * dG * Yin[P];
-    Yout[P] = (rhoj[P] / dt - off) / (((T)ph.rho_ref + r1[P]) / dt + T(0.5625) * dG);
+    Yout[P] = (rhoj[P] / dt - off) / (((T)(st + mem_)->rho_ref + r1[P]) / dt + T(0.5625) * dG);
     END_CELLS
 }
 
@@ -849,6 +897,7 @@ __global__ void __launch_bounds__(kBlock) k_dust_sweep(Phys ph, const DevState* 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dust_faceflux(Phys ph, const T* __restrict__ Y,
                                                           T* __restrict__ G) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
     FOR_CELLS(ph)
 #pragma unroll
@@ -862,8 +911,9 @@ __global__ void __launch_bounds__(kBlock) k_dust_finish(Phys ph, const DevState*
                                                         const T* __restrict__ rhoj,
                                                         const T* __restrict__ F, T* __restrict__ rhoj1,
                                                         double* partials) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
-    const T dt = (T)st->dt, inv_V = (T)ph.inv_V;
+    const T dt = (T)(st + mem_)->dt, inv_V = (T)ph.inv_V;
     double v[1] = {0.0};
     FOR_CELLS(ph)
     T dF = T(0);
@@ -879,9 +929,10 @@ __global__ void __launch_bounds__(kBlock) k_dust_finish(Phys ph, const DevState*
 // ---------------------------------------------------------------- statistics
 // Partial sums of rho|u|^2/2, |curl u|^2/2 (Gauss-I4), |u|^2 and r.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_stats_gas(Phys ph,
+__global__ void __launch_bounds__(kBlock) k_stats_gas(Phys ph, const DevState* st,
                                                       const T* __restrict__ r,
                                                       const T* __restrict__ u, double* partials) {
+    MEMBER(ph)
     const size_t N = ncell(ph);
     const T inv_h = (T)ph.inv_h;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -893,7 +944,7 @@ __global__ void __launch_bounds__(kBlock) k_stats_gas(Phys ph,
     const double wy = (double)(dgauss(ux, c, 2, inv_h) - dgauss(uz, c, 0, inv_h));
     const double wz = (double)(dgauss(uy, c, 0, inv_h) - dgauss(ux, c, 1, inv_h));
     const double q = (double)ux[P] * ux[P] + (double)uy[P] * uy[P] + (double)uz[P] * uz[P];
-    v[0] += 0.5 * (ph.rho_ref + (double)r[P]) * q;
+    v[0] += 0.5 * ((st + mem_)->rho_ref + (double)r[P]) * q;
     v[1] += 0.5 * (wx * wx + wy * wy + wz * wz);
     v[2] += q;
     v[3] += (double)r[P];
@@ -901,10 +952,14 @@ __global__ void __launch_bounds__(kBlock) k_stats_gas(Phys ph,
     block_partials<4, 0u>(v, partials);
 }
 
-// Partial sums of (a x + b)^2 and of x.
+// Partial sums of (a x + b)^2 and of x, with per-member (a, b) = st[m].aff when
+// st is given, else the arguments.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sum_affine_sq(Phys ph, const T* __restrict__ x,
-                                                          double a, double b, double* partials) {
+__global__ void __launch_bounds__(kBlock) k_sum_affine_sq(Phys ph, const DevState* st,
+                                                          const T* __restrict__ x, double a0,
+                                                          double b0, double* partials) {
+    MEMBER(ph)
+    const double a = st ? (st + mem_)->aff[0] : a0, b = st ? (st + mem_)->aff[1] : b0;
     double v[2] = {0.0, 0.0};
     FOR_CELLS(ph)
     const double y = a * (double)x[P] + b;
@@ -914,60 +969,191 @@ __global__ void __launch_bounds__(kBlock) k_sum_affine_sq(Phys ph, const T* __re
     block_partials<2, 0u>(v, partials);
 }
 
-// One block: totals of nv partial columns (sums) into dst[0..nv-1].
-__global__ void __launch_bounds__(kBlock) k_finalize_sums(const double* part, unsigned nb, int nv,
-                                                          double* dst) {
+// One block per member: totals of nv partial columns (sums) of member
+// blockIdx.x into st[member].red[off .. off + nv).
+__global__ void __launch_bounds__(kBlock) k_finalize_sums(const double* part, unsigned nbt,
+                                                          int batch, int nv, DevState* st, int off) {
+    const int m = blockIdx.x;
     for (int c = 0; c < nv; ++c) {
         double t[1];
-        reduce_partials<1, 0u>(part + (size_t)c * nb, nb, t);
-        if (flat_tid() == 0) dst[c] = t[0];
+        reduce_member<1, 0u>(part + (size_t)c * nbt, nbt, batch, m, t);
+        if (flat_tid() == 0) st[m].red[off + c] = t[0];
     }
 }
 
-// One block at the end of a step: mass budget, divergence flags and the dust
-// class masses from the partials of the last corrector and the dust finish.
+// Total of nb partials into dst[0] (one block).
+__global__ void __launch_bounds__(kBlock) k_sum_partials(const double* part, unsigned nb,
+                                                         double* dst) {
+    double t[1];
+    reduce_partials<1, 0u>(part, nb, t);
+    if (flat_tid() == 0) dst[0] = t[0];
+}
+
+// One block per member at the end of a step: mass budget, divergence flags
+// and the dust class masses from the partials of the last corrector and of
+// the dust finish.
 __global__ void __launch_bounds__(kBlock) k_step_finish(Phys ph, DevState* st,
                                                         const double* part_mass,
                                                         const double* part_dust, int ncls,
-                                                        unsigned nb, size_t cls_stride) {
+                                                        unsigned nbt, size_t cls_stride) {
+    const int m = blockIdx.x;
+    DevState* sm = st + m;
     double v[3];
-    reduce_partials<3, 4u>(part_mass, nb, v);
+    reduce_member<3, 4u>(part_mass, nbt, ph.batch, m, v);
     if (flat_tid() == 0) {
-        st->mass_gas = (ph.rho_ref * (double)ncell(ph) + v[0]) * ph.V;
-        st->usq = v[1];
-        st->rho_min = -v[2];
-        if (!isfinite(v[0]) || !isfinite(v[1])) st->flags |= 2;
-        if (!(-v[2] > 0.0)) st->flags |= 4;
+        sm->mass_gas = (sm->rho_ref * (double)ph.N + v[0]) * ph.V;
+        sm->usq = v[1];
+        sm->rho_min = -v[2];
+        if (!isfinite(v[0]) || !isfinite(v[1])) sm->flags |= 2;
+        if (!(-v[2] > 0.0)) sm->flags |= 4;
     }
     for (int c = 0; c < ncls; ++c) {
-        double m[1];
-        reduce_partials<1, 0u>(part_dust + (size_t)c * cls_stride, nb, m);
-        if (flat_tid() == 0) st->mass_p[c] = m[0] * ph.V;
+        double mm[1];
+        reduce_member<1, 0u>(part_dust + (size_t)c * cls_stride, nbt, ph.batch, m, mm);
+        if (flat_tid() == 0) sm->mass_p[c] = mm[0] * ph.V;
+    }
+}
+
+// Accept the step of every member: t += dt, dt_prev = dt, and fold the step
+// record into the accumulators (one thread per member).
+__global__ void k_commit(DevState* st, int batch) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= batch) return;
+    DevState& d = st[m];
+    d.t += d.dt;
+    d.dt_prev = d.dt;
+    d.flags_acc |= d.flags;
+    d.steps_acc += 1;
+    for (int c = 0; c < kMaxCorr; ++c) {
+        if (d.it_first[c] > d.it_first_max[c]) d.it_first_max[c] = d.it_first[c];
+        if (d.it_later[c] > d.it_later_max[c]) d.it_later_max[c] = d.it_later[c];
+    }
+}
+
+// Clear the accumulators of every member.
+__global__ void k_clear_acc(DevState* st, int batch) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= batch) return;
+    DevState& d = st[m];
+    d.flags_acc = 0;
+    d.steps_acc = 0;
+    for (int c = 0; c < kMaxCorr; ++c) {
+        d.it_first_max[c] = 0;
+        d.it_later_max[c] = 0;
+    }
+}
+
+// Per-member affine coefficients for k_sum_affine_sq from the totals in red[]:
+// mode 0: (1, -red[3]/N) (deviation from the mean of r); mode 1: (0, 0) (plain
+// sums); mode 2: (1/mean, -1) with mean = red[5]/N (relative deviation).
+__global__ void k_set_affine(DevState* st, int batch, int mode, double N) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= batch) return;
+    double a = 0.0, b = 0.0;
+    if (mode == 0) {
+        a = 1.0;
+        b = -st[m].red[3] / N;
+    } else if (mode == 2) {
+        const double mean = st[m].red[5] / N;
+        a = mean != 0.0 ? 1.0 / mean : 0.0;
+        b = mean != 0.0 ? -1.0 : 0.0;
+    }
+    st[m].aff[0] = a;
+    st[m].aff[1] = b;
+}
+
+// Record a solve of corrector `corr` in every member's step record.
+// add: the solve just finished counts -- its iterations are added to the
+// step's total and kept as the first solve's (round <= 1: the FP64 solve or
+// the first FP32 round) or as the largest later round's.  fin (1: residual
+// from the last CG check, 2: from red[0] = ||r64||^2 after refinement):
+// the final relative residual against the original ||b|| and the refinement
+// rounds (round) are stored, and flag 1 is raised unless the residual meets
+// the requested tolerance.
+__global__ void k_record_solve(DevState* st, int batch, int corr, int round, int add, int fin) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= batch) return;
+    DevState& d = st[m];
+    if (add) {
+        const int it = d.pcg.iters;
+        d.it_corr[corr] += it;
+        if (round <= 1) d.it_first[corr] = it;
+        else if (it > d.it_later[corr]) d.it_later[corr] = it;
+    }
+    if (!fin) return;
+    const double rr = fin == 2 ? d.red[0] : d.pcg.rr;
+    d.rel_corr[corr] = d.pcg.bb > 0.0 ? sqrt(rr / d.pcg.bb) : 0.0;
+    d.rounds_corr[corr] = round;
+    if (!(rr <= d.pcg.tol_final * d.pcg.bb)) d.flags |= 1;
+}
+
+// Tolerance of the next FP32 refinement round of every member from red[0] =
+// ||r64||^2 and the original ||b||^2 (pcg.bb): reduce the current residual
+// to half the requested one, but by no less than the factor tau_min (and at
+// least by 1/2); a member already within p_tol gets a tolerance the solve
+// meets at once.
+__global__ void k_set_tol_refine(DevState* st, int batch, double tau_min) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= batch) return;
+    DevState& d = st[m];
+    const double rr = d.red[0], bb = d.pcg.bb;
+    if (rr <= d.pcg.tol_final * bb || !(bb > 0.0)) {
+        d.pcg.tol2 = 1.0;
+        return;
+    }
+    double tau = 0.5 * sqrt(d.pcg.tol_final * bb / rr);
+    tau = tau < tau_min ? tau_min : (tau > 0.5 ? 0.5 : tau);
+    d.pcg.tol2 = tau * tau * (rr / bb);
+}
+
+// Set the CG tolerance (squared, relative to the reference ||b||) of every member.
+__global__ void k_set_tol(DevState* st, int batch, double tol2) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < batch) st[m].pcg.tol2 = tol2;
+}
+
+// Clear the step flags and the step record of every member (start of a step).
+__global__ void k_clear_flags(DevState* st, int batch) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= batch) return;
+    st[m].flags = 0;
+    for (int c = 0; c < kMaxCorr; ++c) {
+        st[m].it_corr[c] = 0;
+        st[m].rel_corr[c] = 0.0;
+        st[m].rounds_corr[c] = 0;
+        st[m].it_first[c] = 0;
+        st[m].it_later[c] = 0;
     }
 }
 
 // ------------------------------------------------------------------------
 // launch wrappers
 // ------------------------------------------------------------------------
-Launch make_launch(int n) {
+Launch make_launch_shaped(int n, int batch, int bx, int cz) {
     Launch L;
-    const int bx = n >= 64 ? 64 : 32;
     const int by = kBlock / bx;
     const int gx = (n + bx - 1) / bx, gy = (n + by - 1) / by;
-    // about kTargetBlocks blocks: the partials of a reduction stay small enough
-    // for every block of the consuming kernel to total them redundantly
-    int nz = kTargetBlocks / (gx * gy);
-    nz = nz < 1 ? 1 : (nz > n ? n : nz);
-    const int cz = (n + nz - 1) / nz;
-    nz = (n + cz - 1) / cz;
+    cz = cz < 1 ? 1 : (cz > n ? n : cz);
+    const int nz = (n + cz - 1) / cz;
     L.block = dim3(bx, by, 1);
-    L.grid = dim3(gx, gy, nz);
+    L.grid = dim3(gx, gy, nz * batch);
     L.nblocks = L.grid.x * L.grid.y * L.grid.z;
     L.cz = cz;
+    L.nz = nz;
     return L;
 }
 
-Launch make_tiled_launch(int n) {
+Launch make_launch(int n, int batch) {
+    const int bx = n >= 64 ? 64 : 32;
+    const int gx = (n + bx - 1) / bx, gy = (n + kBlock / bx - 1) / (kBlock / bx);
+    // about kTargetBlocks blocks per member: the partials of a reduction stay
+    // small enough for every block of the consuming kernel to total them
+    int nz = kTargetBlocks / (gx * gy);
+    nz = nz < 1 ? 1 : (nz > n ? n : nz);
+    return make_launch_shaped(n, batch, bx, (n + nz - 1) / nz);
+}
+
+Launch make_tiled_launch(int n, int batch) {
     Launch L{};
     if (n < 128 || n % kTX != 0 || n % kTY != 0) return L;   // nblocks = 0: not available
     const int gx = n / kTX, gy = n / kTY;
@@ -977,9 +1163,10 @@ Launch make_tiled_launch(int n) {
     if (cz < 8) cz = 8;
     nz = (n + cz - 1) / cz;
     L.block = dim3(kTX, kTY, 1);
-    L.grid = dim3(gx, gy, nz);
+    L.grid = dim3(gx, gy, nz * batch);
     L.nblocks = L.grid.x * L.grid.y * L.grid.z;
     L.cz = cz;
+    L.nz = nz;
     return L;
 }
 
@@ -1001,26 +1188,28 @@ void Ops<T>::cast_out(hipStream_t s, const T* src, double* dst, size_t count, do
     hipLaunchKernelGGL(k_cast_out<T>, lin_grid(count), dim3(kBlock), 0, s, src, dst, count, shift);
 }
 template <typename T>
-void Ops<T>::pressure_out(hipStream_t s, const Phys& ph, const T* r, double* dst) {
-    size_t N = ncell(ph);
-    hipLaunchKernelGGL(k_pressure_out<T>, lin_grid(N), dim3(kBlock), 0, s, ph, r, dst, N);
+void Ops<T>::pressure_out(hipStream_t s, const Phys& ph, double rho_ref, double p_ref, const T* r,
+                          double* dst) {
+    hipLaunchKernelGGL(k_pressure_out<T>, lin_grid(ph.N), dim3(kBlock), 0, s, ph.gamma, rho_ref,
+                       p_ref, r, dst, ph.N);
 }
 template <typename T>
-void Ops<T>::init_phi(const Launch& L, hipStream_t s, const Phys& ph, const T* r, const T* u, T* phi) {
-    LAUNCH(k_init_phi<T>, L, s, ph, r, u, phi);
+void Ops<T>::init_phi(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                      const T* r, const T* u, T* phi) {
+    LAUNCH(k_init_phi<T>, L, s, ph, st, r, u, phi);
 }
 template <typename T>
-void Ops<T>::cfl(const Launch& L, hipStream_t s, const Phys& ph, const T* r, const T* phi,
-                 double* part) {
-    LAUNCH(k_cfl<T>, L, s, ph, r, phi, part);
+void Ops<T>::cfl(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st, const T* r,
+                 const T* phi, double* part) {
+    LAUNCH(k_cfl<T>, L, s, ph, st, r, phi, part);
 }
 template <typename T>
 void Ops<T>::predict(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                      const double* part_cfl, double dt_fixed, double cfl, double growth,
-                     double dt_prev, double dt_max, const T* rn, const T* un, const T* phi, T* rs,
-                     T* aP, T* divu, T* pn) {
-    LAUNCH(k_predict<T>, L, s, ph, st, part_cfl, L.nblocks, dt_fixed, cfl, growth, dt_prev, dt_max,
-           rn, un, phi, rs, aP, divu, pn);
+                     double dt_max, const T* rn, const T* un, const T* phi, T* rs, T* aP, T* divu,
+                     T* pn) {
+    LAUNCH(k_predict<T>, L, s, ph, st, part_cfl, L.nblocks, dt_fixed, cfl, growth, dt_max, rn, un,
+           phi, rs, aP, divu, pn);
 }
 template <typename T>
 void Ops<T>::mom_source(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
@@ -1028,15 +1217,18 @@ void Ops<T>::mom_source(const Launch& L, hipStream_t s, const Phys& ph, const De
     LAUNCH(k_mom_source<T>, L, s, ph, st, rn, un, divu, src);
 }
 template <typename T>
-void Ops<T>::mom_sweep(const Launch& L, hipStream_t s, const Phys& ph, const T* uin, T* uout,
-                       const T* phi, const T* aP, const T* src, const T* pn) {
-    LAUNCH((k_mom_sweep<T, false>), L, s, ph, uin, uout, phi, aP, src, pn, (const T*)nullptr,
+void Ops<T>::mom_sweep(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                       const T* uin, T* uout, const T* phi, const T* aP, const T* src,
+                       const T* pn) {
+    LAUNCH((k_mom_sweep<T, false>), L, s, ph, st, uin, uout, phi, aP, src, pn, (const T*)nullptr,
            (T*)nullptr, (T*)nullptr);
 }
 template <typename T>
-void Ops<T>::hbya(const Launch& L, hipStream_t s, const Phys& ph, const T* uin, T* hb,
-                  const T* phi, const T* aP, const T* src, const T* rk, T* w, T* p0) {
-    LAUNCH((k_mom_sweep<T, true>), L, s, ph, uin, hb, phi, aP, src, (const T*)nullptr, rk, w, p0);
+void Ops<T>::hbya(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                  const T* uin, T* hb, const T* phi, const T* aP, const T* src, const T* rk, T* w,
+                  T* p0) {
+    LAUNCH((k_mom_sweep<T, true>), L, s, ph, st, uin, hb, phi, aP, src, (const T*)nullptr, rk, w,
+           p0);
 }
 template <typename T>
 void Ops<T>::corr_rhs(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, const T* rn,
@@ -1059,15 +1251,16 @@ void Ops<T>::zero(hipStream_t s, T* a, size_t count) {
 template <typename T>
 void Ops<T>::pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                       DevState* st, int k, const T* r, const T* diag, const T* w, const T* pold,
-                      T* pnew, T* q, const double* part_u, double* part_s, double tol2, int maxit) {
+                      T* pnew, T* q, const double* part_u, double* part_s, int fresh, int maxit) {
     if (TL.nblocks) {
         Phys pt = ph;
         pt.cz = TL.cz;
+        pt.nz = TL.nz;
         LAUNCH(k_pcg_spmv_tiled<T>, TL, s, pt, st, k, r, diag, w, pold, pnew, q, part_u, L.nblocks,
-               part_s, tol2, maxit);
+               part_s, fresh, maxit);
     } else {
         LAUNCH(k_pcg_spmv<T>, L, s, ph, st, k, r, diag, w, pold, pnew, q, part_u, part_s,
-               L.nblocks, tol2, maxit);
+               L.nblocks, fresh, maxit);
     }
 }
 template <typename T>
@@ -1108,9 +1301,10 @@ void Ops<T>::dudt(const Launch& L, hipStream_t s, const Phys& ph, const DevState
     LAUNCH(k_dudt<T>, L, s, ph, st, un, u1, acc);
 }
 template <typename T>
-void Ops<T>::dust_flux(const Launch& L, hipStream_t s, const Phys& ph, double tau, const T* phi,
-                       const T* r1, const T* acc, T* G, const T* rhoj, const T* rn, T* Y) {
-    LAUNCH(k_dust_flux<T>, L, s, ph, tau, phi, r1, acc, G, rhoj, rn, Y);
+void Ops<T>::dust_flux(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st, int cls,
+                       const T* phi, const T* r1, const T* acc, T* G, const T* rhoj, const T* rn,
+                       T* Y) {
+    LAUNCH(k_dust_flux<T>, L, s, ph, st, cls, phi, r1, acc, G, rhoj, rn, Y);
 }
 template <typename T>
 void Ops<T>::dust_sweep(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
@@ -1127,23 +1321,51 @@ void Ops<T>::dust_finish(const Launch& L, hipStream_t s, const Phys& ph, const D
     LAUNCH(k_dust_finish<T>, L, s, ph, st, rhoj, F, rhoj1, part);
 }
 template <typename T>
-void Ops<T>::stats_gas(const Launch& L, hipStream_t s, const Phys& ph, const T* r, const T* u,
-                       double* part) {
-    LAUNCH(k_stats_gas<T>, L, s, ph, r, u, part);
+void Ops<T>::stats_gas(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                       const T* r, const T* u, double* part) {
+    LAUNCH(k_stats_gas<T>, L, s, ph, st, r, u, part);
 }
 template <typename T>
-void Ops<T>::sum_affine_sq(const Launch& L, hipStream_t s, const Phys& ph, const T* x, double a,
-                           double b, double* part) {
-    LAUNCH(k_sum_affine_sq<T>, L, s, ph, x, a, b, part);
+void Ops<T>::sum_affine_sq(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                           const T* x, double a, double b, double* part) {
+    LAUNCH(k_sum_affine_sq<T>, L, s, ph, st, x, a, b, part);
 }
 
-void finalize_sums(hipStream_t s, const double* part, unsigned nb, int nv, double* dst) {
-    hipLaunchKernelGGL(k_finalize_sums, dim3(1), dim3(64, 4), 0, s, part, nb, nv, dst);
+void finalize_sums(hipStream_t s, const double* part, unsigned nbt, int batch, int nv,
+                   DevState* st, int off) {
+    hipLaunchKernelGGL(k_finalize_sums, dim3(batch), dim3(64, 4), 0, s, part, nbt, batch, nv, st,
+                       off);
+}
+void sum_partials(hipStream_t s, const double* part, unsigned nb, double* dst) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64, 4), 0, s, part, nb, dst);
 }
 void step_finish(hipStream_t s, const Phys& ph, DevState* st, const double* part_mass,
-                 const double* part_dust, int ncls, unsigned nb, size_t cls_stride) {
-    hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(64, 4), 0, s, ph, st, part_mass, part_dust,
-                       ncls, nb, cls_stride);
+                 const double* part_dust, int ncls, unsigned nbt, size_t cls_stride) {
+    hipLaunchKernelGGL(k_step_finish, dim3(ph.batch), dim3(64, 4), 0, s, ph, st, part_mass,
+                       part_dust, ncls, nbt, cls_stride);
+}
+void commit(hipStream_t s, DevState* st, int batch) {
+    hipLaunchKernelGGL(k_commit, dim3((batch + 63) / 64), dim3(64), 0, s, st, batch);
+}
+void clear_acc(hipStream_t s, DevState* st, int batch) {
+    hipLaunchKernelGGL(k_clear_acc, dim3((batch + 63) / 64), dim3(64), 0, s, st, batch);
+}
+void set_tol_refine(hipStream_t s, DevState* st, int batch, double tau_min) {
+    hipLaunchKernelGGL(k_set_tol_refine, dim3((batch + 63) / 64), dim3(64), 0, s, st, batch,
+                       tau_min);
+}
+void set_tol(hipStream_t s, DevState* st, int batch, double tol2) {
+    hipLaunchKernelGGL(k_set_tol, dim3((batch + 63) / 64), dim3(64), 0, s, st, batch, tol2);
+}
+void set_affine(hipStream_t s, DevState* st, int batch, int mode, double N) {
+    hipLaunchKernelGGL(k_set_affine, dim3((batch + 63) / 64), dim3(64), 0, s, st, batch, mode, N);
+}
+void record_solve(hipStream_t s, DevState* st, int batch, int corr, int round, int add, int fin) {
+    hipLaunchKernelGGL(k_record_solve, dim3((batch + 63) / 64), dim3(64), 0, s, st, batch, corr,
+                       round, add, fin);
+}
+void clear_flags(hipStream_t s, DevState* st, int batch) {
+    hipLaunchKernelGGL(k_clear_flags, dim3((batch + 63) / 64), dim3(64), 0, s, st, batch);
 }
 
 template <typename T>
@@ -1171,9 +1393,10 @@ void Ops<T>::guess_apply(const Launch& L, hipStream_t s, const Phys& ph, DevStat
            part_u);
 }
 template <typename T>
-void Ops<T>::guess_revert(const Launch& L, hipStream_t s, const Phys& ph, T* r, T* x, double* x64,
-                          const double* b64, const T* bsave, const T* diag, double* part_u) {
-    LAUNCH(k_guess_revert<T>, L, s, ph, r, x, x64, b64, bsave, diag, part_u);
+void Ops<T>::guess_revert(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, T* r,
+                          T* x, double* x64, const double* b64, const T* bsave, const T* diag,
+                          double* part_u) {
+    LAUNCH(k_guess_revert<T>, L, s, ph, st, r, x, x64, b64, bsave, diag, part_u);
 }
 
 template struct Ops<double>;

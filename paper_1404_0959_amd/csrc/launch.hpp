@@ -13,8 +13,9 @@ namespace pisoc {
 
 struct Launch {
     dim3 grid, block;
-    unsigned nblocks;
-    int cz;
+    unsigned nblocks;   // all members
+    int cz;             // cells per thread along z
+    int nz;             // blocks per member along z
 };
 
 constexpr int kTargetBlocks = 2048;
@@ -23,11 +24,15 @@ constexpr int kTiledBlocks = 1024;
 
 // Blocks of 64x4 (n >= 64) or 32x8 threads over x-y; each thread walks cz
 // consecutive cells along z, with cz chosen for about kTargetBlocks blocks.
-Launch make_launch(int n);
+Launch make_launch(int n, int batch = 1);
+
+// The same kernels with blocks of bx x (kBlock / bx) threads and cz cells per
+// thread along z (bx a power of two in 16..256, 1 <= cz <= n).
+Launch make_launch_shaped(int n, int batch, int bx, int cz);
 
 // Launch of the LDS-tiled z-marching kernels (64 x 8 threads per block); nblocks
 // is 0 when n is not a multiple of the tile or below 128.
-Launch make_tiled_launch(int n);
+Launch make_tiled_launch(int n, int batch = 1);
 
 // Partial-sum slots in the workspace (columns of num_blocks doubles each).
 enum PartSlot {
@@ -44,21 +49,25 @@ template <typename T>
 struct Ops {
     static void cast_in(hipStream_t s, const double* src, T* dst, size_t count, double shift);
     static void cast_out(hipStream_t s, const T* src, double* dst, size_t count, double shift);
-    static void pressure_out(hipStream_t s, const Phys& ph, const T* r, double* dst);
-    static void init_phi(const Launch& L, hipStream_t s, const Phys& ph, const T* r, const T* u,
-                         T* phi);
-    static void cfl(const Launch& L, hipStream_t s, const Phys& ph, const T* r, const T* phi,
-                    double* part);
+    // one member's pressure p_ref + p_dev(r) (r points at the member's cells)
+    static void pressure_out(hipStream_t s, const Phys& ph, double rho_ref, double p_ref,
+                             const T* r, double* dst);
+    static void init_phi(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                         const T* r, const T* u, T* phi);
+    static void cfl(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                    const T* r, const T* phi, double* part);
     static void predict(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                         const double* part_cfl, double dt_fixed, double cfl, double growth,
-                        double dt_prev, double dt_max, const T* rn, const T* un, const T* phi,
-                        T* rs, T* aP, T* divu, T* pn);
+                        double dt_max, const T* rn, const T* un, const T* phi, T* rs, T* aP,
+                        T* divu, T* pn);
     static void mom_source(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                            const T* rn, const T* un, const T* divu, T* src);
-    static void mom_sweep(const Launch& L, hipStream_t s, const Phys& ph, const T* uin, T* uout,
-                          const T* phi, const T* aP, const T* src, const T* pn);
-    static void hbya(const Launch& L, hipStream_t s, const Phys& ph, const T* uin, T* hb,
-                     const T* phi, const T* aP, const T* src, const T* rk, T* w, T* p0);
+    static void mom_sweep(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                          const T* uin, T* uout, const T* phi, const T* aP, const T* src,
+                          const T* pn);
+    static void hbya(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                     const T* uin, T* hb, const T* phi, const T* aP, const T* src, const T* rk,
+                     T* w, T* p0);
     static void corr_rhs(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                          const T* rn, const T* rk, const T* w, const T* hb, const T* p0, T* phiH,
                          T* r, T* x, T* diag, double* part_u, double* snap_b, double* snap_diag,
@@ -71,7 +80,7 @@ struct Ops {
     static void pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                          DevState* st, int k, const T* r, const T* diag, const T* w,
                          const T* pold, T* pnew, T* q, const double* part_u, double* part_s,
-                         double tol2, int maxit);
+                         int fresh, int maxit);
     static void pcg_update(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                            const DevState* st, int k, T* r, const T* q, const T* diag, T* x,
                            const T* p, const double* part_s, double* part_u);
@@ -87,18 +96,19 @@ struct Ops {
                             const T* aP, T* rk, T* u, double* part_mass);
     static void dudt(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                      const T* un, const T* u1, T* acc);
-    static void dust_flux(const Launch& L, hipStream_t s, const Phys& ph, double tau,
-                          const T* phi, const T* r1, const T* acc, T* G, const T* rhoj,
+    static void dust_flux(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                          int cls, const T* phi, const T* r1, const T* acc, T* G, const T* rhoj,
                           const T* rn, T* Y);
     static void dust_sweep(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                            const T* Yin, T* Yout, const T* G, const T* rhoj, const T* r1);
     static void dust_faceflux(const Launch& L, hipStream_t s, const Phys& ph, const T* Y, T* G);
     static void dust_finish(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                             const T* rhoj, const T* F, T* rhoj1, double* part);
-    static void stats_gas(const Launch& L, hipStream_t s, const Phys& ph, const T* r, const T* u,
-                          double* part);
-    static void sum_affine_sq(const Launch& L, hipStream_t s, const Phys& ph, const T* x,
-                              double a, double b, double* part);
+    static void stats_gas(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                          const T* r, const T* u, double* part);
+    // st non-null: per-member (a, b) = st[m].aff
+    static void sum_affine_sq(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                              const T* x, double a, double b, double* part);
     // learned guess
     static void net_stats(const Launch& L, hipStream_t s, const Phys& ph, const T* b,
                           const T* diag, const T* p0, double* part);
@@ -111,15 +121,35 @@ struct Ops {
     static void guess_apply(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                             const double* part_g, const T* g, const T* mg, const T* diag, T* r,
                             T* x, double* x64, const double* b64, T* bsave, double* part_u);
-    static void guess_revert(const Launch& L, hipStream_t s, const Phys& ph, T* r, T* x,
-                             double* x64, const double* b64, const T* bsave, const T* diag,
-                             double* part_u);
+    // per member, where the guess does not lower ||r|| (totals in st[m].red[1..2])
+    static void guess_revert(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, T* r,
+                             T* x, double* x64, const double* b64, const T* bsave,
+                             const T* diag, double* part_u);
 };
 
-// One-block totals of nv partial columns into dst (device).
-void finalize_sums(hipStream_t s, const double* part, unsigned nb, int nv, double* dst);
-// One-block end-of-step mass budget and flags.
+// Per member: totals of nv partial columns (written by a launch of nbt blocks
+// over `batch` members) into st[m].red[off ..].
+void finalize_sums(hipStream_t s, const double* part, unsigned nbt, int batch, int nv,
+                   DevState* st, int off);
+// Total of nb partials (one column) into dst[0].
+void sum_partials(hipStream_t s, const double* part, unsigned nb, double* dst);
+// Per member: end-of-step mass budget and flags.
 void step_finish(hipStream_t s, const Phys& ph, DevState* st, const double* part_mass,
-                 const double* part_dust, int ncls, unsigned nb, size_t cls_stride);
+                 const double* part_dust, int ncls, unsigned nbt, size_t cls_stride);
+// Per member: t += dt, dt_prev = dt (the step is accepted); fold the step
+// record into the accumulators.
+void commit(hipStream_t s, DevState* st, int batch);
+// Per member: clear the accumulators.
+void clear_acc(hipStream_t s, DevState* st, int batch);
+// Per member: tolerance of the next FP32 refinement round (see k_set_tol_refine).
+void set_tol_refine(hipStream_t s, DevState* st, int batch, double tau_min);
+// Per member: CG tolerance (squared) for the next solve.
+void set_tol(hipStream_t s, DevState* st, int batch, double tol2);
+// Per member: affine coefficients for sum_affine_sq (see k_set_affine).
+void set_affine(hipStream_t s, DevState* st, int batch, int mode, double N);
+// Per member: record a solve of corrector corr in the step record (see k_record_solve).
+void record_solve(hipStream_t s, DevState* st, int batch, int corr, int round, int add, int fin);
+// Per member: clear the step flags.
+void clear_flags(hipStream_t s, DevState* st, int batch);
 
 }  // namespace pisoc

@@ -415,7 +415,7 @@ pisoc_status pisoc_net_grad(int32_t n, int32_t batch, const float* d_w, const fl
     hipLaunchKernelGGL(k_mse, dim3(L.lblocks), B, 0, s, y, d_t, cells, (float)(2.0 / (double)cells),
                        U(L.dy), lpart);
     double* loss_dev = lpart + L.lblocks;
-    finalize_sums(s, lpart, L.lblocks, 1, loss_dev);
+    sum_partials(s, lpart, L.lblocks, loss_dev);
     // backward: layer 4 (linear), 3, 2, 1
     float* part = reinterpret_cast<float*>(ws + L.part);
     const dim3 GW((L.nwaves + 3) / 4);

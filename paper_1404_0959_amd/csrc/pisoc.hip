@@ -2,10 +2,22 @@
 //
 // The library owns no device memory: every field, the CG vectors, the
 // reduction partials and the device-side state live in the caller's
-// workspace.  All work is enqueued on the caller's stream.  The host waits on
-// the stream only to learn when a pressure solve has converged (one wait per
-// batch of CG iterations, whose size is predicted from the previous solve) and
-// at the end of each step, to check it before committing it.
+// workspace.
+//
+// A context holds `batch` members of one grid size stacked along z: every
+// kernel covers all of them in one launch, and every per-member quantity (dt,
+// the reference density and pressure, particle response times, the CG state)
+// lives in the member's DevState.  Two ways of running a step share one launch
+// sequence:
+//  - eager (pisoc_step, the ensemble's calibration): the host waits on the
+//    stream only to learn when every member's pressure solve has stopped (one
+//    wait per batch of CG iterations, sized from the previous solve), between
+//    FP64 refinement rounds, and at the end of the step to check it before
+//    committing it;
+//  - captured (ensembles): CG to a fixed iteration cap with early exit per
+//    member, a fixed number of refinement rounds, the commit on the device;
+//    captured once per buffer parity into one HIP graph for all size classes
+//    (one branch per class) and replayed, one graph launch per step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,10 +40,25 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr unsigned kMaxTuneBlocks = 4096;   // blocks per member of a launch-shape candidate
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Byte offsets of every buffer inside the workspace.
+// Launch-shape candidates of the field kernels for grid size n: (bx, cz).
+std::vector<std::pair<int, int>> shape_candidates(int n) {
+    std::vector<std::pair<int, int>> out;
+    for (int bx : {16, 32, 64, 128}) {
+        if (bx > 2 * n) continue;
+        for (int cz : {1, 2, 4, 8, 16}) {
+            if (cz > n) continue;
+            const Launch L = make_launch_shaped(n, 1, bx, cz);
+            if (L.nblocks <= kMaxTuneBlocks) out.push_back({bx, cz});
+        }
+    }
+    return out;
+}
+
+// Byte offsets of every buffer inside the workspace (all members of a batch).
 struct Layout {
     size_t state, partials;
     size_t rn, rk, aP, divu, pn, w, p0, r, x, diag, pp0, pp1, q, Y0, Y1;
@@ -41,9 +68,8 @@ struct Layout {
     size_t b64, x64a, x64b;  // FP64 refinement fields (FP32 storage only)
     size_t wpk, nx4, na, nb, ny, bsave;  // learned guess: packed weights, activations
     size_t total;
-    unsigned max_blocks;
+    unsigned max_blocks;     // column length of the partials (all members)
 };
-
 
 // Kernel classes for the optional per-launch event timing.
 enum KCls {
@@ -121,15 +147,17 @@ bool valid_params(const pisoc_params* p, std::string* why) {
     return true;
 }
 
-Layout make_layout(const pisoc_params* p) {
+Layout make_layout(const pisoc_params* p, int batch) {
     Layout L{};
-    const size_t N = (size_t)p->n * p->n * p->n;
+    const size_t N = (size_t)p->n * p->n * p->n * (size_t)batch;
     const size_t es = p->precision == PISOC_FP64 ? sizeof(double) : sizeof(float);
-    const Launch lc = make_launch(p->n);
-    L.max_blocks = std::max(lc.nblocks, make_tiled_launch(p->n).nblocks);
+    unsigned mb = std::max(make_launch(p->n, batch).nblocks, make_tiled_launch(p->n, batch).nblocks);
+    for (auto [bx, cz] : shape_candidates(p->n))
+        mb = std::max(mb, make_launch_shaped(p->n, batch, bx, cz).nblocks);
+    L.max_blocks = mb;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
-    L.state = take(sizeof(DevState));
+    L.state = take(sizeof(DevState) * (size_t)batch);
     L.partials = take(sizeof(double) * PS_COLUMNS * (size_t)L.max_blocks);
     size_t* one[] = {&L.rn, &L.rk, &L.aP, &L.divu, &L.pn, &L.w, &L.p0, &L.r, &L.x, &L.diag,
                      &L.pp0, &L.pp1, &L.q, &L.Y0, &L.Y1};
@@ -161,6 +189,7 @@ Layout make_layout(const pisoc_params* p) {
 
 struct pisoc_ctx {
     pisoc_params prm;
+    int batch = 1;
     hipStream_t stream;
     char* ws;
     Layout lay;
@@ -168,22 +197,29 @@ struct pisoc_ctx {
     Launch L;
     Launch TL;      // tiled z-marching launch (nblocks = 0 when not available)
     DevState* st;
-    DevState* hst;  // pinned host copy
+    DevState* hst = nullptr;  // pinned host copy (batch entries)
     double* partials;
     // rotating buffers
     int u_idx[3];   // which of lay.u3 holds u^n, work a, work b
+    int ucur_slot;  // u_idx slot holding u* after the predictor sweeps (1 or 2)
     size_t rn, rk, phin, phik, rhop, rhop1;
-    double t, dt_prev;
+    double t;
     int64_t steps;
-    int last_iters[PISOC_MAX_CORR];
-    int last_first[PISOC_MAX_CORR];  // FP32 mode: iterations of the first inner solve
+    int pred_first[PISOC_MAX_CORR];  // CG iterations of the last first solve (all members)
+    int pred_later;                  // ... of the last later refinement round
+    // captured mode: CG pairs per first solve, per later round, refinement rounds
+    int caps[PISOC_MAX_CORR];
+    int cap_later;
+    int rounds;
     size_t es;      // bytes per field element (8 or 4)
     Prof prof;
     std::string err;
+    std::vector<double> rho_ref, p_ref;  // per member
 
     template <typename T> T* f(size_t off) const { return reinterpret_cast<T*>(ws + off); }
     size_t N() const { return (size_t)prm.n * prm.n * prm.n; }
-    // partial-sum column `slot` (num_blocks doubles per column)
+    size_t NT() const { return N() * (size_t)batch; }
+    // partial-sum column `slot` (max_blocks doubles per column)
     double* part(int slot) const { return partials + (size_t)slot * lay.max_blocks; }
 };
 
@@ -216,21 +252,25 @@ void timed(pisoc_ctx* ctx, int cls, double words, int k, F&& launch) {
     (void)hipEventRecord(P.pool[a], ctx->stream);
     launch();
     (void)hipEventRecord(P.pool[b], ctx->stream);
-    P.pending.push_back({cls, a, b, words * (double)ctx->es * (double)ctx->N(), k});
+    P.pending.push_back({cls, a, b, words * (double)ctx->es * (double)ctx->NT(), k});
 }
 
 pisoc_status sync_state(pisoc_ctx* ctx) {
     HIP_TRY(ctx, hipGetLastError());
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->hst, ctx->st, sizeof(DevState), hipMemcpyDeviceToHost,
-                                ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->hst, ctx->st, sizeof(DevState) * (size_t)ctx->batch,
+                                hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return PISOC_OK;
 }
 
-Phys make_phys(const pisoc_params* p, double rho_ref) {
+Phys make_phys(const pisoc_params* p, const Launch& L, int batch) {
     Phys ph{};
     ph.n = p->n;
-    ph.cz = make_launch(p->n).cz;
+    ph.cz = L.cz;
+    ph.nz = L.nz;
+    ph.batch = batch;
+    ph.N = (size_t)p->n * p->n * p->n;
+    ph.NT = ph.N * (size_t)batch;
     ph.h = kTwoPi / p->n;
     ph.inv_h = 1.0 / ph.h;
     ph.inv_h2 = 1.0 / (ph.h * ph.h);
@@ -240,19 +280,26 @@ Phys make_phys(const pisoc_params* p, double rho_ref) {
     ph.gamma = p->gamma;
     ph.C = p->C;
     ph.mu = p->mu;
-    ph.rho_ref = rho_ref;
-    ph.p_ref = p->C * std::pow(rho_ref, p->gamma);
     return ph;
 }
 
-// CG on the system already set up by corr_rhs / helm_start (which left the
-// partials r0.z0, r0.r0, b.b).  Launches the first half of iteration 0, then
-// batches of (second half k, first half k+1) pairs; the first half of k+1
-// tests convergence, so a batch always ends on a test.  Launches after the
-// stop return at once.
+void set_shape(pisoc_ctx* ctx, const Launch& L) {
+    ctx->L = L;
+    ctx->ph.cz = L.cz;
+    ctx->ph.nz = L.nz;
+}
+
+// CG on the system already set up by corr_rhs / helm_start / guess_apply /
+// k_refine (which left the partials r0.z0, r0.r0, b.b), to the tolerance
+// already set in each member's state.  Launches the first half of iteration
+// 0, then (second half k, first half k+1) pairs; the first half of k+1 tests
+// convergence, and every launch after a member's stop returns at once for
+// that member.  eager: pairs in batches, the first sized `pairs`, the host
+// waiting after each until every member has stopped; otherwise exactly
+// `pairs` pairs (capture).  Returns the largest iteration count (eager).
 template <typename T>
-pisoc_status run_pcg(pisoc_ctx* ctx, T* r, T* x, T* diag, T* w, T* pp0, T* pp1, T* q,
-                     double tol, int predicted, int32_t* iters, double* relres, bool* converged) {
+pisoc_status run_pcg(pisoc_ctx* ctx, T* r, T* x, T* diag, T* w, T* pp0, T* pp1, T* q, bool fresh,
+                     int pairs, bool eager, int* iters_max) {
     using O = Ops<T>;
     const int maxit = ctx->prm.p_maxit;
     T* pp[2] = {pp0, pp1};
@@ -261,7 +308,7 @@ pisoc_status run_pcg(pisoc_ctx* ctx, T* r, T* x, T* diag, T* w, T* pp0, T* pp1, 
     auto spmv = [&](int k) {
         timed(ctx, KC_PCG_SPMV, k == 0 ? 5.0 : 6.0, k, [&] {
             O::pcg_spmv(ctx->L, ctx->TL, ctx->stream, ctx->ph, ctx->st, k, r, diag, w,
-                        pp[(k + 1) & 1], pp[k & 1], q, pu, ps, tol * tol, maxit);
+                        pp[(k + 1) & 1], pp[k & 1], q, pu, ps, fresh ? 1 : 0, maxit);
         });
     };
     auto update = [&](int k) {
@@ -272,7 +319,16 @@ pisoc_status run_pcg(pisoc_ctx* ctx, T* r, T* x, T* diag, T* w, T* pp0, T* pp1, 
     };
     spmv(0);
     int k = 0;  // first halves launched: 0..k
-    int batch = std::max(1, predicted);
+    if (!eager) {
+        const int cap = std::min(std::max(1, pairs), maxit);
+        for (; k < cap; ++k) {
+            update(k);
+            spmv(k + 1);
+        }
+        return PISOC_OK;
+    }
+    int batch = std::max(1, pairs);
+    int most = 0;
     for (;;) {
         const int kend = std::min(k + batch, maxit);
         for (; k < kend; ++k) {
@@ -281,82 +337,29 @@ pisoc_status run_pcg(pisoc_ctx* ctx, T* r, T* x, T* diag, T* w, T* pp0, T* pp1, 
         }
         pisoc_status s = sync_state(ctx);
         if (s != PISOC_OK) return s;
-        if (ctx->prof.on) ctx->prof.resolve(ctx->hst->pcg.it_stop);
-        if (ctx->hst->flags & PISOC_FLAG_BAD_DT) break;
-        if (ctx->hst->pcg.it_stop != kIterInf || k >= maxit) break;
+        bool all = true, bad_dt = false;
+        int stop_max = 0;
+        for (int m = 0; m < ctx->batch; ++m) {
+            all = all && ctx->hst[m].pcg.it_stop != kIterInf;
+            stop_max = std::max(stop_max, ctx->hst[m].pcg.it_stop);
+            bad_dt = bad_dt || (ctx->hst[m].flags & PISOC_FLAG_BAD_DT);
+        }
+        // launches with k >= the latest stop did no work for any member
+        if (ctx->prof.on) ctx->prof.resolve(all ? stop_max : kIterInf);
+        if (all || bad_dt || k >= maxit) break;
         batch = 2;
     }
-    const PcgState& g = ctx->hst->pcg;
-    *iters = g.iters;
-    *relres = g.bb > 0.0 ? std::sqrt(g.rr / g.bb) : 0.0;
-    *converged = g.converged != 0;
+    for (int m = 0; m < ctx->batch; ++m) most = std::max(most, ctx->hst[m].pcg.iters);
+    if (iters_max) *iters_max = most;
     return PISOC_OK;
 }
 
-// FP32 storage: mixed-precision iterative refinement of M p' = b.  Inner
-// solves are FP32 CG to a relative tolerance tau; after each, k_refine adds the
-// correction to the FP64 accumulator and evaluates the true residual in FP64;
-// the loop ends when ||r64|| <= p_tol ||b64||.
-pisoc_status refine_solve(pisoc_ctx* ctx, float* r, float* x, float* diag, float* w, float* pp0,
-                          float* pp1, float* q, int corr, int32_t* iters, double* relres,
-                          bool* converged, int32_t* rounds) {
-    const pisoc_params& p = ctx->prm;
-    double* b64 = ctx->f<double>(ctx->lay.b64);
-    double* xa = ctx->f<double>(ctx->lay.x64a);
-    double* xb = ctx->f<double>(ctx->lay.x64b);
-    const size_t N = ctx->N();
-    int32_t it = 0, total = 0;
-    double rel = 0.0;
-    bool conv = false;
-    const int pred0 = ctx->last_first[corr] > 0 ? ctx->last_first[corr] : 8;
-    const double tau0 = std::min(0.5, std::max(0.5 * p.p_tol, p.inner_tol));
-    pisoc_status st = run_pcg<float>(ctx, r, x, diag, w, pp0, pp1, q, tau0, pred0, &it, &rel,
-                                     &conv);
-    if (st != PISOC_OK) return st;
-    ctx->last_first[corr] = it;
-    total += it;
-    const double bb = ctx->hst->pcg.bb;
-    double rr = bb;
-    int nround = 0;
-    if (bb > 0.0) {
-        for (;;) {
-            timed(ctx, KC_REFINE, 10, -1, [&] {
-                Ops<float>::refine(ctx->L, ctx->stream, ctx->ph, ctx->st, xa, x, xb, b64, w, diag, r,
-                                   ctx->part(PS_U));
-            });
-            std::swap(xa, xb);
-            // column 1 (||r64||^2) of the 3-column block written with L.nblocks blocks
-            finalize_sums(ctx->stream, ctx->part(PS_U) + ctx->L.nblocks, ctx->L.nblocks, 1,
-                          ctx->st->red);
-            if ((st = sync_state(ctx)) != PISOC_OK) return st;
-            if (ctx->prof.on) ctx->prof.resolve(kIterInf);
-            rr = ctx->hst->red[0];
-            ++nround;
-            if (rr <= p.p_tol * p.p_tol * bb || nround >= p.max_refine || !std::isfinite(rr)) break;
-            double tau = 0.5 * p.p_tol * std::sqrt(bb / rr);
-            tau = std::min(0.5, std::max(tau, p.inner_tol));
-            Ops<float>::zero(ctx->stream, x, N);
-            st = run_pcg<float>(ctx, r, x, diag, w, pp0, pp1, q, tau, 2, &it, &rel, &conv);
-            if (st != PISOC_OK) return st;
-            total += it;
-        }
-    }
-    // the corrector uses the FP32 copy of the FP64 solution
-    Ops<float>::cast_in(ctx->stream, xa, x, N, 0.0);
-    *iters = total;
-    *relres = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
-    *converged = rr <= p.p_tol * p.p_tol * bb;
-    *rounds = nround;
-    return PISOC_OK;
-}
-
-// The learned initial guess of one pressure solve: scaled inputs from the
-// system just set up, the network on the matrix cores, CG restarted from
-// x0 = alpha s1 y (alpha energy-optimal); rejected (back to x0 = 0) unless
-// ||b - M x0|| < ||b||.
+// The learned initial guess of one pressure solve, every member: scaled inputs
+// from the system just set up, the network on the matrix cores, CG started from
+// x0 = alpha s1 y (alpha energy-optimal); a member whose guess does not lower
+// ||b - M x0|| below ||b|| falls back to x0 = 0 (decided on the device).
 template <typename T>
-pisoc_status learned_guess(pisoc_ctx* ctx, T* r, T* x, T* dg, T* w, T* p0, T* gbuf, T* mgbuf,
-                           int* flags) {
+void learned_guess(pisoc_ctx* ctx, T* r, T* x, T* dg, T* w, T* p0, T* gbuf, T* mgbuf) {
     using O = Ops<T>;
     const Layout& Y = ctx->lay;
     const bool f32 = sizeof(T) == sizeof(float);
@@ -368,182 +371,867 @@ pisoc_status learned_guess(pisoc_ctx* ctx, T* r, T* x, T* dg, T* w, T* p0, T* gb
         O::net_stats(ctx->L, s, ctx->ph, r, dg, p0, ctx->part(PS_STAT));
         O::net_input(ctx->L, s, ctx->ph, ctx->st, ctx->part(PS_STAT), r, dg, p0,
                      ctx->f<uint16_t>(Y.nx4), nullptr, nullptr, nullptr);
-        net_forward(s, ctx->prm.n, 1, ctx->ws + Y.wpk, ctx->f<uint16_t>(Y.nx4),
+        net_forward(s, ctx->prm.n, ctx->batch, ctx->ws + Y.wpk, ctx->f<uint16_t>(Y.nx4),
                     ctx->f<uint16_t>(Y.na), ctx->f<uint16_t>(Y.nb), ctx->f<float>(Y.ny), 1.f);
         O::guess_start(ctx->L, s, ctx->ph, ctx->st, ctx->f<float>(Y.ny), w, dg, r, b64, gbuf,
                        mgbuf, ctx->part(PS_STAT));
         O::guess_apply(ctx->L, s, ctx->ph, ctx->st, ctx->part(PS_STAT), gbuf, mgbuf, dg, r, x,
                        x64, b64, bsave, ctx->part(PS_U));
+        // totals of r0.z0, ||r0||^2, ||b||^2 into red[0..2], then the fallback test
+        finalize_sums(s, ctx->part(PS_U), ctx->L.nblocks, ctx->batch, 3, ctx->st, 0);
+        O::guess_revert(ctx->L, s, ctx->ph, ctx->st, r, x, x64, b64, bsave, dg, ctx->part(PS_U));
     });
-    // totals of r0.z0, ||r0||^2, ||b||^2 (3 columns written with L.nblocks blocks)
-    const unsigned nb = ctx->L.nblocks;
-    finalize_sums(s, ctx->part(PS_U), nb, 3, ctx->st->red);
-    pisoc_status st = sync_state(ctx);
-    if (st != PISOC_OK) return st;
-    if (ctx->prof.on) ctx->prof.resolve(kIterInf);
-    const double rr = ctx->hst->red[1], bb = ctx->hst->red[2];
-    if (!(rr < bb)) {
-        *flags |= PISOC_FLAG_GUESS_FALLBACK;
-        O::guess_revert(ctx->L, s, ctx->ph, r, x, x64, b64, bsave, dg, ctx->part(PS_U));
-    }
-    return PISOC_OK;
 }
 
+// Pointers of the current buffer rotation.
 template <typename T>
-pisoc_status one_step(pisoc_ctx* ctx, pisoc_step_info* info) {
+struct StepPtrs {
+    T *rn, *rk, *un, *ua, *ub, *phin, *phik;
+    T *aP, *divu, *pn, *src, *hb, *w, *p0, *phiH, *r, *x, *dg, *pp0, *pp1, *q;
+    T *acc, *G, *Ya, *Yb, *rj, *rj1;
+    double *snap, *b64, *x64a, *x64b;
+};
+
+template <typename T>
+StepPtrs<T> step_ptrs(const pisoc_ctx* ctx) {
+    const Layout& Y = ctx->lay;
+    auto F = [&](size_t off) { return ctx->f<T>(off); };
+    StepPtrs<T> P;
+    P.rn = F(ctx->rn);
+    P.rk = F(ctx->rk);
+    P.un = F(Y.u3[ctx->u_idx[0]]);
+    P.ua = F(Y.u3[ctx->u_idx[1]]);
+    P.ub = F(Y.u3[ctx->u_idx[2]]);
+    P.phin = F(ctx->phin);
+    P.phik = F(ctx->phik);
+    P.aP = F(Y.aP);
+    P.divu = F(Y.divu);
+    P.pn = F(Y.pn);
+    P.src = F(Y.src);
+    P.hb = F(Y.hbya);
+    P.w = F(Y.w);
+    P.p0 = F(Y.p0);
+    P.phiH = F(Y.phiH);
+    P.r = F(Y.r);
+    P.x = F(Y.x);
+    P.dg = F(Y.diag);
+    P.pp0 = F(Y.pp0);
+    P.pp1 = F(Y.pp1);
+    P.q = F(Y.q);
+    P.acc = F(Y.acc);
+    P.G = F(Y.G);
+    P.Ya = F(Y.Y0);
+    P.Yb = F(Y.Y1);
+    P.rj = F(ctx->rhop);
+    P.rj1 = F(ctx->rhop1);
+    P.snap = ctx->prm.capture ? reinterpret_cast<double*>(ctx->ws + Y.snap) : nullptr;
+    const bool f32 = sizeof(T) == sizeof(float);
+    P.b64 = f32 ? ctx->f<double>(Y.b64) : nullptr;
+    P.x64a = f32 ? ctx->f<double>(Y.x64a) : nullptr;
+    P.x64b = f32 ? ctx->f<double>(Y.x64b) : nullptr;
+    return P;
+}
+
+// dt, density predictor, momentum source and predictor sweeps (u* ends in
+// the u slot ctx->ucur_slot).
+template <typename T>
+void enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S) {
     using O = Ops<T>;
     const pisoc_params& p = ctx->prm;
     const Phys& ph = ctx->ph;
     const Launch& L = ctx->L;
     hipStream_t s = ctx->stream;
-    const size_t N = ctx->N();
     DevState* st = ctx->st;
-    auto F = [&](size_t off) { return ctx->f<T>(off); };
-    const Layout& Y = ctx->lay;
-
-    T* rn = F(ctx->rn);
-    T* rk = F(ctx->rk);
-    T* un = F(Y.u3[ctx->u_idx[0]]);
-    T* ua = F(Y.u3[ctx->u_idx[1]]);
-    T* ub = F(Y.u3[ctx->u_idx[2]]);
-    T* phin = F(ctx->phin);
-    T* phik = F(ctx->phik);
-    T *aP = F(Y.aP), *divu = F(Y.divu), *pn = F(Y.pn), *src = F(Y.src), *hb = F(Y.hbya);
-    T *w = F(Y.w), *p0 = F(Y.p0), *phiH = F(Y.phiH), *r = F(Y.r), *x = F(Y.x), *dg = F(Y.diag);
-    T *pp0 = F(Y.pp0), *pp1 = F(Y.pp1), *q = F(Y.q);
-    double* snap = p.capture ? reinterpret_cast<double*>(ctx->ws + Y.snap) : nullptr;
-    const bool f32 = sizeof(T) == sizeof(float);
-
-    pisoc_step_info rec{};
-    int flags = 0;
-    pisoc_status worst = PISOC_OK;
-
-    HIP_TRY(ctx, hipMemsetAsync(&st->flags, 0, sizeof(int32_t), s));
-    timed(ctx, KC_CFL, 4, -1, [&] { O::cfl(L, s, ph, rn, phin, ctx->part(PS_CFL)); });
+    clear_flags(s, st, ctx->batch);
+    timed(ctx, KC_CFL, 4, -1, [&] { O::cfl(L, s, ph, st, S.rn, S.phin, ctx->part(PS_CFL)); });
     timed(ctx, KC_PREDICT, 11, -1, [&] {
-        O::predict(L, s, ph, st, ctx->part(PS_CFL), p.dt_fixed, p.cfl, p.dt_growth, ctx->dt_prev,
-                   p.dt_max, rn, un, phin, rk, aP, divu, pn);
+        O::predict(L, s, ph, st, ctx->part(PS_CFL), p.dt_fixed, p.cfl, p.dt_growth, p.dt_max, S.rn,
+                   S.un, S.phin, S.rk, S.aP, S.divu, S.pn);
     });
-    timed(ctx, KC_MOM_SOURCE, 8, -1, [&] { O::mom_source(L, s, ph, st, rn, un, divu, src); });
-    T* uin = un;
+    timed(ctx, KC_MOM_SOURCE, 8, -1, [&] { O::mom_source(L, s, ph, st, S.rn, S.un, S.divu, S.src); });
+    T* uin = S.un;
     for (int i = 0; i < p.n_mom_sweeps; ++i) {
-        T* uout = (i & 1) ? ub : ua;
-        timed(ctx, KC_MOM_SWEEP, 14, -1, [&] { O::mom_sweep(L, s, ph, uin, uout, phin, aP, src, pn); });
+        T* uout = (i & 1) ? S.ub : S.ua;
+        timed(ctx, KC_MOM_SWEEP, 14, -1,
+              [&] { O::mom_sweep(L, s, ph, st, uin, uout, S.phin, S.aP, S.src, S.pn); });
         uin = uout;
     }
-    T* ucur = uin;
-    const int ucur_slot = (ucur == ua) ? 1 : 2;
+}
 
-    for (int corr = 0; corr < p.n_corr; ++corr) {
-        timed(ctx, KC_HBYA, 16, -1, [&] { O::hbya(L, s, ph, ucur, hb, phin, aP, src, rk, w, p0); });
-        const bool cap = snap && corr == 0;
-        timed(ctx, KC_CORR_RHS, f32 ? 17 : 13, -1, [&] {
-            O::corr_rhs(L, s, ph, st, rn, rk, w, hb, p0, phiH, r, x, dg, ctx->part(PS_U),
-                        cap ? snap : nullptr, cap ? snap + N : nullptr,
-                        cap ? snap + 2 * N : nullptr, f32 ? ctx->f<double>(Y.b64) : nullptr,
-                        f32 ? ctx->f<double>(Y.x64a) : nullptr);
-        });
-        if (p.guess == PISOC_GUESS_LEARNED) {
-            pisoc_status gs = learned_guess<T>(ctx, r, x, dg, w, p0, pp0, q, &flags);
-            if (gs != PISOC_OK) return gs;
-            if (flags & PISOC_FLAG_GUESS_FALLBACK) worst = std::max(worst, PISOC_WARN_GUESS_FALLBACK);
-        }
-        int32_t it = 0, rounds = 0;
-        double rel = 0.0;
-        bool conv = false;
-        const int pred = ctx->last_iters[corr] > 0 ? ctx->last_iters[corr] : 8;
-        pisoc_status ps;
-        if constexpr (sizeof(T) == sizeof(float))
-            ps = refine_solve(ctx, r, x, dg, w, pp0, pp1, q, corr, &it, &rel, &conv, &rounds);
-        else
-            ps = run_pcg<T>(ctx, r, x, dg, w, pp0, pp1, q, p.p_tol, pred, &it, &rel, &conv);
-        if (ps != PISOC_OK) return ps;
-        rec.refinements[corr] = rounds;
-        if (ctx->hst->flags & PISOC_FLAG_BAD_DT) {
-            ctx->err = "time step undefined or non-positive (zero velocity needs dt_fixed or dt_max)";
-            return PISOC_ERR_INVALID;
-        }
-        ctx->last_iters[corr] = it;
-        rec.pcg_iters[corr] = it;
-        rec.pcg_relres[corr] = rel;
-        if (!conv) {
-            flags |= PISOC_FLAG_PCG_MAXIT;
-            worst = PISOC_WARN_NOT_CONVERGED;
-        }
-        timed(ctx, KC_CORR_FLUX, 10, -1, [&] {
-            O::corr_flux(L, s, ph, p0, x, w, phiH, phik, q, cap ? snap + 3 * N : nullptr);
-        });
-        timed(ctx, KC_CORR_UPDATE, 13, -1, [&] {
-            O::corr_update(L, s, ph, st, corr == p.n_corr - 1, rn, phik, hb, q, aP, rk, ucur,
-                           ctx->part(PS_MASS));
-        });
-    }
+template <typename T>
+T* ucur_of(const pisoc_ctx* ctx, StepPtrs<T>& S) { return ctx->ucur_slot == 1 ? S.ua : S.ub; }
 
+template <typename T>
+void enqueue_corr_setup(pisoc_ctx* ctx, StepPtrs<T>& S, int corr) {
+    using O = Ops<T>;
+    const Phys& ph = ctx->ph;
+    const Launch& L = ctx->L;
+    hipStream_t s = ctx->stream;
+    const size_t N = ctx->NT();
+    const bool f32 = sizeof(T) == sizeof(float);
+    T* ucur = ucur_of(ctx, S);
+    timed(ctx, KC_HBYA, 16, -1,
+          [&] { O::hbya(L, s, ph, ctx->st, ucur, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0); });
+    const bool cap = S.snap && corr == 0;
+    timed(ctx, KC_CORR_RHS, f32 ? 17 : 13, -1, [&] {
+        O::corr_rhs(L, s, ph, ctx->st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH, S.r, S.x, S.dg,
+                    ctx->part(PS_U), cap ? S.snap : nullptr, cap ? S.snap + N : nullptr,
+                    cap ? S.snap + 2 * N : nullptr, S.b64, S.x64a);
+    });
+    if (ctx->prm.guess == PISOC_GUESS_LEARNED)
+        learned_guess<T>(ctx, S.r, S.x, S.dg, S.w, S.p0, S.pp0, S.q);
+}
+
+template <typename T>
+void enqueue_corr_finish(pisoc_ctx* ctx, StepPtrs<T>& S, int corr) {
+    using O = Ops<T>;
+    const Phys& ph = ctx->ph;
+    const Launch& L = ctx->L;
+    hipStream_t s = ctx->stream;
+    const size_t N = ctx->NT();
+    const bool cap = S.snap && corr == 0;
+    T* ucur = ucur_of(ctx, S);
+    timed(ctx, KC_CORR_FLUX, 10, -1, [&] {
+        O::corr_flux(L, s, ph, S.p0, S.x, S.w, S.phiH, S.phik, S.q, cap ? S.snap + 3 * N : nullptr);
+    });
+    timed(ctx, KC_CORR_UPDATE, 13, -1, [&] {
+        O::corr_update(L, s, ph, ctx->st, corr == ctx->prm.n_corr - 1, S.rn, S.phik, S.hb, S.q, S.aP,
+                       S.rk, ucur, ctx->part(PS_MASS));
+    });
+}
+
+template <typename T>
+void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
+    using O = Ops<T>;
+    const pisoc_params& p = ctx->prm;
+    const Phys& ph = ctx->ph;
+    const Launch& L = ctx->L;
+    hipStream_t s = ctx->stream;
+    DevState* st = ctx->st;
+    const size_t N = ctx->NT();
+    T* ucur = ucur_of(ctx, S);
     if (p.n_classes > 0) {
-        T* acc = F(Y.acc);
-        T* G = F(Y.G);
-        T* Ya = F(Y.Y0);
-        T* Yb = F(Y.Y1);
-        T* rj = F(ctx->rhop);
-        T* rj1 = F(ctx->rhop1);
-        timed(ctx, KC_DUDT, 9, -1, [&] { O::dudt(L, s, ph, st, un, ucur, acc); });
+        timed(ctx, KC_DUDT, 9, -1, [&] { O::dudt(L, s, ph, st, S.un, ucur, S.acc); });
         for (int c = 0; c < p.n_classes; ++c) {
             timed(ctx, KC_DUST_FLUX, 13, -1, [&] {
-                O::dust_flux(L, s, ph, p.tau_p[c], phik, rk, acc, G, rj + c * N, rn, Ya);
+                O::dust_flux(L, s, ph, st, c, S.phik, S.rk, S.acc, S.G, S.rj + c * N, S.rn, S.Ya);
             });
-            T* yin = Ya;
-            T* yout = Yb;
+            T* yin = S.Ya;
+            T* yout = S.Yb;
             for (int i = 0; i < p.n_dust_sweeps; ++i) {
                 timed(ctx, KC_DUST_SWEEP, 7, -1,
-                      [&] { O::dust_sweep(L, s, ph, st, yin, yout, G, rj + c * N, rk); });
+                      [&] { O::dust_sweep(L, s, ph, st, yin, yout, S.G, S.rj + c * N, S.rk); });
                 std::swap(yin, yout);
             }
-            timed(ctx, KC_DUST_FACEFLUX, 7, -1, [&] { O::dust_faceflux(L, s, ph, yin, G); });
-            timed(ctx, KC_DUST_FINISH, 5, -1,
-                  [&] { O::dust_finish(L, s, ph, st, rj + c * N, G, rj1 + c * N, ctx->part(PS_DUST + c)); });
+            timed(ctx, KC_DUST_FACEFLUX, 7, -1, [&] { O::dust_faceflux(L, s, ph, yin, S.G); });
+            timed(ctx, KC_DUST_FINISH, 5, -1, [&] {
+                O::dust_finish(L, s, ph, st, S.rj + c * N, S.G, S.rj1 + c * N, ctx->part(PS_DUST + c));
+            });
         }
     }
     step_finish(s, ph, st, ctx->part(PS_MASS), ctx->part(PS_DUST), p.n_classes, L.nblocks,
-                Y.max_blocks);
+                ctx->lay.max_blocks);
+}
 
-    pisoc_status ss = sync_state(ctx);
-    if (ss != PISOC_OK) return ss;
-    if (ctx->prof.on) ctx->prof.resolve(kIterInf);
-    const DevState& h = *ctx->hst;
-    flags |= h.flags;
-    if (h.flags & PISOC_FLAG_BAD_DT) {
-        ctx->err = "time step undefined or non-positive";
-        return PISOC_ERR_INVALID;
-    }
-    bool bad = (h.flags & (PISOC_FLAG_NONFINITE | PISOC_FLAG_RHO_NONPOS)) != 0;
-    for (int c = 0; c < p.n_classes; ++c)
-        if (!std::isfinite(h.mass_p[c])) bad = true;
-    if (bad) {
-        ctx->err = "step diverged (non-finite field or non-positive density); state kept";
-        if (info) {
-            rec.flags = flags | PISOC_FLAG_NONFINITE;
-            rec.dt = h.dt;
-            rec.t = ctx->t;
-            *info = rec;
+// FP32 storage: mixed-precision iterative refinement of M p' = b for every
+// member.  The first inner FP32 solve runs to tau0 = max(p_tol/2, inner_tol)
+// of ||b||; after each inner solve k_refine adds the correction to the FP64
+// accumulator and evaluates the true residual in FP64; each later round aims
+// at half the requested residual (reducing the current one by no more than
+// the factor inner_tol); a member is done when ||r64|| <= p_tol ||b||.
+// eager: rounds until every member is done or max_refine; otherwise exactly
+// ctx->rounds rounds with ctx->caps / cap_later CG pairs.  The FP64 solution
+// ends in x64a and its FP32 copy in x.
+void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool eager, pisoc_status* err) {
+    const pisoc_params& p = ctx->prm;
+    hipStream_t s = ctx->stream;
+    const int B = ctx->batch;
+    double* xa = S.x64a;
+    double* xb = S.x64b;
+    const double tau0 = std::min(0.5, std::max(0.5 * p.p_tol, p.inner_tol));
+    *err = PISOC_OK;
+    set_tol(s, ctx->st, B, tau0 * tau0);
+    int most = 0;
+    const int pairs0 = eager ? (ctx->pred_first[corr] > 0 ? ctx->pred_first[corr] : 8) : ctx->caps[corr];
+    if ((*err = run_pcg<float>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, true, pairs0, eager,
+                               &most)) != PISOC_OK)
+        return;
+    if (eager) ctx->pred_first[corr] = most;
+    record_solve(s, ctx->st, B, corr, /*round=*/1, /*add=*/1, /*fin=*/0);
+    const int max_rounds = eager ? p.max_refine : ctx->rounds;
+    int round = 0;
+    for (;;) {
+        timed(ctx, KC_REFINE, 10, -1, [&] {
+            Ops<float>::refine(ctx->L, s, ctx->ph, ctx->st, xa, S.x, xb, S.b64, S.w, S.dg, S.r,
+                               ctx->part(PS_U));
+        });
+        std::swap(xa, xb);
+        ++round;
+        // column 1 (||r64||^2) of the 3 columns written with L.nblocks blocks
+        finalize_sums(s, ctx->part(PS_U) + ctx->L.nblocks, ctx->L.nblocks, B, 1, ctx->st, 0);
+        if (round >= max_rounds) break;
+        if (eager) {
+            if ((*err = sync_state(ctx)) != PISOC_OK) return;
+            if (ctx->prof.on) ctx->prof.resolve(kIterInf);
+            bool done = true;
+            for (int m = 0; m < B; ++m) {
+                const DevState& h = ctx->hst[m];
+                if (!(h.red[0] <= h.pcg.tol_final * h.pcg.bb) && std::isfinite(h.red[0])) done = false;
+            }
+            if (done) break;
         }
-        return PISOC_ERR_DIVERGED;
+        set_tol_refine(s, ctx->st, B, p.inner_tol);
+        Ops<float>::zero(s, S.x, ctx->NT());
+        const int pairs = eager ? std::max(2, ctx->pred_later) : ctx->cap_later;
+        if ((*err = run_pcg<float>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, false, pairs, eager,
+                                   &most)) != PISOC_OK)
+            return;
+        if (eager) ctx->pred_later = most;
+        record_solve(s, ctx->st, B, corr, round + 1, /*add=*/1, /*fin=*/0);
     }
-    // commit
+    record_solve(s, ctx->st, B, corr, round, /*add=*/0, /*fin=*/2);
+    // the corrector uses the FP32 copy of the FP64 solution
+    Ops<float>::cast_in(s, xa, S.x, ctx->NT(), 0.0);
+}
+
+// Launch sequence of one step of every member.  eager: with host waits in the
+// pressure solves; otherwise the fixed sequence for graph capture.
+template <typename T>
+pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
+    const pisoc_params& p = ctx->prm;
+    StepPtrs<T> S = step_ptrs<T>(ctx);
+    hipStream_t s = ctx->stream;
+    enqueue_front<T>(ctx, S);
+    for (int corr = 0; corr < p.n_corr; ++corr) {
+        enqueue_corr_setup<T>(ctx, S, corr);
+        pisoc_status err = PISOC_OK;
+        if constexpr (sizeof(T) == sizeof(float)) {
+            solve_fp32(ctx, S, corr, eager, &err);
+        } else {
+            set_tol(s, ctx->st, ctx->batch, p.p_tol * p.p_tol);
+            int most = 0;
+            const int pairs =
+                eager ? (ctx->pred_first[corr] > 0 ? ctx->pred_first[corr] : 8) : ctx->caps[corr];
+            err = run_pcg<T>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, true, pairs, eager, &most);
+            if (eager) ctx->pred_first[corr] = most;
+            record_solve(s, ctx->st, ctx->batch, corr, /*round=*/0, /*add=*/1, /*fin=*/1);
+        }
+        if (err != PISOC_OK) return err;
+        if (eager) {
+            for (int m = 0; m < ctx->batch; ++m)
+                if (ctx->hst[m].flags & PISOC_FLAG_BAD_DT) {
+                    ctx->err = "time step undefined or non-positive (zero velocity needs dt_fixed "
+                               "or dt_max)";
+                    return PISOC_ERR_INVALID;
+                }
+        }
+        enqueue_corr_finish<T>(ctx, S, corr);
+    }
+    enqueue_dust<T>(ctx, S);
+    if (!eager) commit(s, ctx->st, ctx->batch);
+    return PISOC_OK;
+}
+
+// Host-side rotation after an accepted step (period 2).
+void rotate(pisoc_ctx* ctx) {
     std::swap(ctx->rn, ctx->rk);
     std::swap(ctx->phin, ctx->phik);
-    std::swap(ctx->u_idx[0], ctx->u_idx[ucur_slot]);
-    if (p.n_classes > 0) std::swap(ctx->rhop, ctx->rhop1);
-    ctx->t += h.dt;
-    ctx->dt_prev = h.dt;
-    ctx->steps += 1;
-    rec.t = ctx->t;
+    std::swap(ctx->u_idx[0], ctx->u_idx[ctx->ucur_slot]);
+    if (ctx->prm.n_classes > 0) std::swap(ctx->rhop, ctx->rhop1);
+}
+
+// Step record of member m from its device state.
+void fill_info(const pisoc_ctx* ctx, const DevState& h, bool committed, pisoc_step_info* out) {
+    pisoc_step_info rec{};
     rec.dt = h.dt;
+    rec.t = committed ? h.t : h.t + h.dt;
     rec.courant = h.sigma * h.dt;
-    rec.flags = flags;
+    rec.flags = h.flags;
     rec.mass_gas = h.mass_gas;
-    for (int c = 0; c < p.n_classes; ++c) rec.mass_p[c] = h.mass_p[c];
-    if (info) *info = rec;
+    for (int c = 0; c < ctx->prm.n_corr; ++c) {
+        rec.pcg_iters[c] = h.it_corr[c];
+        rec.pcg_relres[c] = h.rel_corr[c];
+        rec.refinements[c] = h.rounds_corr[c];
+    }
+    for (int c = 0; c < ctx->prm.n_classes; ++c) rec.mass_p[c] = h.mass_p[c];
+    *out = rec;
+}
+
+bool member_bad(const pisoc_ctx* ctx, const DevState& h) {
+    bool bad = (h.flags & (PISOC_FLAG_NONFINITE | PISOC_FLAG_RHO_NONPOS)) != 0;
+    for (int c = 0; c < ctx->prm.n_classes; ++c)
+        if (!std::isfinite(h.mass_p[c])) bad = true;
+    return bad;
+}
+
+pisoc_status flag_status(int flags) {
+    if (flags & PISOC_FLAG_PCG_MAXIT) return PISOC_WARN_NOT_CONVERGED;
+    if (flags & PISOC_FLAG_GUESS_FALLBACK) return PISOC_WARN_GUESS_FALLBACK;
+    return PISOC_OK;
+}
+
+pisoc_status combine_status(pisoc_status a, pisoc_status b) {
+    if (a < 0 || b < 0) return std::min(a, b);
+    if (a == PISOC_WARN_NOT_CONVERGED || b == PISOC_WARN_NOT_CONVERGED) return PISOC_WARN_NOT_CONVERGED;
+    return std::max(a, b);
+}
+
+// One eager step of every member of ctx; info (may be NULL) receives batch
+// records.  The step is checked before it is committed: if any member
+// diverged, no member advances.
+pisoc_status eager_step(pisoc_ctx* ctx, pisoc_step_info* info) {
+    pisoc_status st = ctx->prm.precision == PISOC_FP64 ? enqueue_step<double>(ctx, true)
+                                                       : enqueue_step<float>(ctx, true);
+    if (st != PISOC_OK) return st;
+    if ((st = sync_state(ctx)) != PISOC_OK) return st;
+    if (ctx->prof.on) ctx->prof.resolve(kIterInf);
+    pisoc_status worst = PISOC_OK;
+    bool bad = false;
+    for (int m = 0; m < ctx->batch; ++m) {
+        const DevState& h = ctx->hst[m];
+        if (h.flags & PISOC_FLAG_BAD_DT) {
+            ctx->err = "time step undefined or non-positive";
+            return PISOC_ERR_INVALID;
+        }
+        if (member_bad(ctx, h)) bad = true;
+        worst = combine_status(worst, flag_status(h.flags));
+    }
+    if (bad) {
+        ctx->err = "step diverged (non-finite field or non-positive density); state kept";
+        if (info)
+            for (int m = 0; m < ctx->batch; ++m) {
+                fill_info(ctx, ctx->hst[m], false, info + m);
+                info[m].t = ctx->hst[m].t;
+                if (member_bad(ctx, ctx->hst[m])) info[m].flags |= PISOC_FLAG_NONFINITE;
+            }
+        return PISOC_ERR_DIVERGED;
+    }
+    if (info)
+        for (int m = 0; m < ctx->batch; ++m) fill_info(ctx, ctx->hst[m], false, info + m);
+    rotate(ctx);
+    commit(ctx->stream, ctx->st, ctx->batch);
+    ctx->t += ctx->hst[0].dt;
+    ctx->steps += 1;
     return worst;
+}
+
+// Common initialisation of a context for `batch` members of one size.
+// mprm[m]: per-member parameters (identical except C and tau_p); inputs per member.
+pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char* ws,
+                      const double* const* d_rho, const double* const* d_u,
+                      const double* const* d_rho_p, hipStream_t stream) {
+    const pisoc_params* prm = &mprm[0];
+    ctx->prm = *prm;
+    ctx->batch = batch;
+    ctx->stream = stream;
+    ctx->ws = ws;
+    ctx->lay = make_layout(prm, batch);
+    const Layout& lay = ctx->lay;
+    ctx->TL = make_tiled_launch(prm->n, batch);
+    // PISOC_UNTILED=1 selects the untiled CG kernel (kernel-comparison tests)
+    if (const char* e = std::getenv("PISOC_UNTILED"); e && e[0] == '1') ctx->TL = Launch{};
+    ctx->L = make_launch(prm->n, batch);
+    ctx->ph = make_phys(prm, ctx->L, batch);
+    ctx->st = reinterpret_cast<DevState*>(ctx->ws + lay.state);
+    ctx->partials = reinterpret_cast<double*>(ctx->ws + lay.partials);
+    ctx->u_idx[0] = 0;
+    ctx->u_idx[1] = 1;
+    ctx->u_idx[2] = 2;
+    ctx->ucur_slot = (prm->n_mom_sweeps & 1) ? 1 : 2;
+    ctx->rn = lay.rn;
+    ctx->rk = lay.rk;
+    ctx->phin = lay.phin;
+    ctx->phik = lay.phik;
+    ctx->rhop = lay.rhop;
+    ctx->rhop1 = lay.rhop1;
+    ctx->t = 0.0;
+    ctx->steps = 0;
+    for (int c = 0; c < PISOC_MAX_CORR; ++c) {
+        ctx->pred_first[c] = 0;
+        ctx->caps[c] = 0;
+    }
+    ctx->pred_later = 0;
+    ctx->cap_later = 0;
+    ctx->rounds = 0;
+    ctx->es = prm->precision == PISOC_FP64 ? sizeof(double) : sizeof(float);
+    ctx->prof.reset();
+    if (hipHostMalloc(reinterpret_cast<void**>(&ctx->hst), sizeof(DevState) * (size_t)batch,
+                      hipHostMallocDefault) != hipSuccess) {
+        ctx->hst = nullptr;
+        ctx->err = "hipHostMalloc failed";
+        return PISOC_ERR_HIP;
+    }
+    hipStream_t s = ctx->stream;
+    const size_t N = ctx->N();
+    HIP_TRY(ctx, hipMemsetAsync(ctx->st, 0, sizeof(DevState) * (size_t)batch, s));
+
+    // reference density of each member = mean of its initial density (FP64)
+    const Launch L1 = make_launch(prm->n, 1);
+    const Phys ph1 = make_phys(prm, L1, 1);
+    for (int m = 0; m < batch; ++m) {
+        Ops<double>::sum_affine_sq(L1, s, ph1, nullptr, d_rho[m], 0.0, 0.0, ctx->part(PS_STAT));
+        finalize_sums(s, ctx->part(PS_STAT), L1.nblocks, 1, 2, ctx->st + m, 0);
+    }
+    pisoc_status ss = sync_state(ctx);
+    if (ss != PISOC_OK) return ss;
+    ctx->rho_ref.assign(batch, 1.0);
+    ctx->p_ref.assign(batch, 1.0);
+    for (int m = 0; m < batch; ++m) {
+        const double rr = ctx->hst[m].red[1] / (double)N;
+        if (!(rr > 0.0) || !std::isfinite(rr)) {
+            ctx->err = "initial density must have a positive finite mean";
+            return PISOC_ERR_INVALID;
+        }
+        ctx->rho_ref[m] = rr;
+        ctx->p_ref[m] = mprm[m].C * std::pow(rr, prm->gamma);
+    }
+    for (int m = 0; m < batch; ++m) {
+        DevState init{};
+        init.pcg.tol2 = prm->p_tol * prm->p_tol;
+        init.pcg.tol_final = prm->p_tol * prm->p_tol;
+        init.pcg.maxit = prm->p_maxit;
+        init.pcg.it_stop = kIterInf;
+        init.dt_prev = __builtin_inf();
+        init.rho_ref = ctx->rho_ref[m];
+        init.p_ref = ctx->p_ref[m];
+        for (int c = 0; c < prm->n_classes; ++c) init.tau[c] = mprm[m].tau_p[c];
+        ctx->hst[m] = init;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->st, ctx->hst, sizeof(DevState) * (size_t)batch,
+                                hipMemcpyHostToDevice, s));
+    const size_t NT = ctx->NT();
+    auto convert = [&](auto tag) {
+        using T = decltype(tag);
+        for (int m = 0; m < batch; ++m) {
+            const size_t off = (size_t)m * N;
+            Ops<T>::cast_in(s, d_rho[m], ctx->f<T>(ctx->rn) + off, N, ctx->rho_ref[m]);
+            for (int d = 0; d < 3; ++d)
+                Ops<T>::cast_in(s, d_u[m] + d * N, ctx->f<T>(lay.u3[0]) + d * NT + off, N, 0.0);
+            for (int c = 0; c < prm->n_classes; ++c)
+                Ops<T>::cast_in(s, d_rho_p[m] + c * N, ctx->f<T>(ctx->rhop) + c * NT + off, N, 0.0);
+        }
+        Ops<T>::init_phi(ctx->L, s, ctx->ph, ctx->st, ctx->f<T>(ctx->rn), ctx->f<T>(lay.u3[0]),
+                         ctx->f<T>(ctx->phin));
+    };
+    if (prm->precision == PISOC_FP64) convert(double{});
+    else convert(float{});
+    if (prm->guess == PISOC_GUESS_LEARNED)
+        net_pack_forward(s, reinterpret_cast<const float*>(prm->d_guess_weights), ctx->ws + lay.wpk);
+    return sync_state(ctx);
+}
+
+void free_ctx(pisoc_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->hst) (void)hipHostFree(ctx->hst);
+    delete ctx;
+}
+
+// Copy out fields of member m (asynchronous).
+pisoc_status member_fields(pisoc_ctx* ctx, int m, uint32_t which, double* const* d_dst) {
+    const size_t N = ctx->N(), NT = ctx->NT(), off = (size_t)m * N;
+    hipStream_t s = ctx->stream;
+    const bool f64 = ctx->prm.precision == PISOC_FP64;
+    int slot = 0;
+    auto cast = [&](size_t boff, size_t comp_off, double* dst, double shift) {
+        if (f64) Ops<double>::cast_out(s, ctx->f<double>(boff) + comp_off + off, dst, N, shift);
+        else Ops<float>::cast_out(s, ctx->f<float>(boff) + comp_off + off, dst, N, shift);
+    };
+    const double* snap = ctx->prm.capture ? reinterpret_cast<double*>(ctx->ws + ctx->lay.snap)
+                                          : nullptr;
+    for (int bit = 0; bit < 32; ++bit) {
+        const uint32_t mk = 1u << bit;
+        if (!(which & mk)) continue;
+        double* dst = d_dst[slot++];
+        if (!dst) {
+            ctx->err = "NULL destination";
+            return PISOC_ERR_INVALID;
+        }
+        switch (mk) {
+            case PISOC_FIELD_RHO: cast(ctx->rn, 0, dst, ctx->rho_ref[m]); break;
+            case PISOC_FIELD_U:
+                for (int d = 0; d < 3; ++d) cast(ctx->lay.u3[ctx->u_idx[0]], d * NT, dst + d * N, 0.0);
+                break;
+            case PISOC_FIELD_PHI:
+                for (int d = 0; d < 3; ++d) cast(ctx->phin, d * NT, dst + d * N, 0.0);
+                break;
+            case PISOC_FIELD_RHO_P:
+                for (int c = 0; c < ctx->prm.n_classes; ++c) cast(ctx->rhop, c * NT, dst + c * N, 0.0);
+                break;
+            case PISOC_FIELD_P:
+                if (f64)
+                    Ops<double>::pressure_out(s, ctx->ph, ctx->rho_ref[m], ctx->p_ref[m],
+                                              ctx->f<double>(ctx->rn) + off, dst);
+                else
+                    Ops<float>::pressure_out(s, ctx->ph, ctx->rho_ref[m], ctx->p_ref[m],
+                                             ctx->f<float>(ctx->rn) + off, dst);
+                break;
+            case PISOC_FIELD_PSOLVE_B:
+            case PISOC_FIELD_PSOLVE_DIAG:
+            case PISOC_FIELD_P_PREV:
+            case PISOC_FIELD_PSOLVE_X: {
+                if (!snap) {
+                    ctx->err = "captured pressure system requested without params.capture";
+                    return PISOC_ERR_INVALID;
+                }
+                const int idx = mk == PISOC_FIELD_PSOLVE_B ? 0
+                                : mk == PISOC_FIELD_PSOLVE_DIAG ? 1
+                                : mk == PISOC_FIELD_P_PREV ? 2 : 3;
+                HIP_TRY(ctx, hipMemcpyAsync(dst, snap + idx * NT + off, N * sizeof(double),
+                                            hipMemcpyDeviceToDevice, s));
+                break;
+            }
+            default: ctx->err = "unknown field bit"; return PISOC_ERR_INVALID;
+        }
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    return PISOC_OK;
+}
+
+// Statistics of every member (FP64 reductions); member m's in out[m].
+pisoc_status all_stats(pisoc_ctx* ctx, pisoc_stats* out) {
+    const double N = (double)ctx->N();
+    const Phys& ph = ctx->ph;
+    hipStream_t s = ctx->stream;
+    const int B = ctx->batch;
+    const bool f64 = ctx->prm.precision == PISOC_FP64;
+    const unsigned nb = ctx->L.nblocks;
+    auto gas = [&](auto tag) {
+        using T = decltype(tag);
+        Ops<T>::stats_gas(ctx->L, s, ph, ctx->st, ctx->f<T>(ctx->rn),
+                          ctx->f<T>(ctx->lay.u3[ctx->u_idx[0]]), ctx->part(PS_STAT));
+    };
+    auto affine = [&](auto tag, size_t boff, size_t comp_off) {
+        using T = decltype(tag);
+        Ops<T>::sum_affine_sq(ctx->L, s, ph, ctx->st, ctx->f<T>(boff) + comp_off, 0.0, 0.0,
+                              ctx->part(PS_STAT));
+    };
+    if (f64) gas(double{}); else gas(float{});
+    finalize_sums(s, ctx->part(PS_STAT), nb, B, 4, ctx->st, 0);
+    // density variance about the member's mean
+    set_affine(s, ctx->st, B, 0, N);
+    if (f64) affine(double{}, ctx->rn, 0); else affine(float{}, ctx->rn, 0);
+    finalize_sums(s, ctx->part(PS_STAT), nb, B, 2, ctx->st, 4);
+    pisoc_status st = sync_state(ctx);
+    if (st != PISOC_OK) return st;
+    for (int m = 0; m < B; ++m) {
+        const DevState& h = ctx->hst[m];
+        pisoc_stats& o = out[m];
+        std::memset(&o, 0, sizeof(o));
+        const double rmean = ctx->rho_ref[m] + h.red[3] / N;
+        const double C = ctx->p_ref[m] / std::pow(ctx->rho_ref[m], ph.gamma);
+        o.ke = h.red[0] / N;
+        o.enstrophy = h.red[1] / N;
+        o.rho_rms = std::sqrt(h.red[4] / N) / rmean;
+        o.mach_rms = std::sqrt(h.red[2] / N) / std::sqrt(ph.gamma * C * std::pow(rmean, ph.gamma - 1.0));
+        o.mass_gas = rmean * N * ph.V;
+    }
+    const size_t NT = ctx->NT();
+    for (int c = 0; c < ctx->prm.n_classes; ++c) {
+        set_affine(s, ctx->st, B, 1, N);
+        if (f64) affine(double{}, ctx->rhop, c * NT); else affine(float{}, ctx->rhop, c * NT);
+        finalize_sums(s, ctx->part(PS_STAT), nb, B, 2, ctx->st, 4);
+        set_affine(s, ctx->st, B, 2, N);
+        if (f64) affine(double{}, ctx->rhop, c * NT); else affine(float{}, ctx->rhop, c * NT);
+        finalize_sums(s, ctx->part(PS_STAT), nb, B, 1, ctx->st, 6);
+        if ((st = sync_state(ctx)) != PISOC_OK) return st;
+        for (int m = 0; m < B; ++m) {
+            const double mean = ctx->hst[m].red[5] / N;
+            out[m].conc_var[c] = mean != 0.0 ? ctx->hst[m].red[6] / N : 0.0;
+            out[m].mass_p[c] = mean * N * ph.V;
+        }
+    }
+    return PISOC_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Launch shapes of the field kernels are tuned per (n, members, precision,
+// dust classes): each candidate (bx, cz) times a representative set of field
+// kernels -- a predictor sweep, H/A, the corrector set-up, two CG iterations
+// and a dust sweep -- on the context's own buffers (all of them scratch
+// between steps; the persistent state is only read), and the fastest wins.
+// Winners are kept in a small JSON object {"key": [bx, cz], ...}.
+std::string tune_key(const pisoc_ctx* ctx) {
+    char b[96];
+    std::snprintf(b, sizeof(b), "n%d_b%d_%s_k%d_g%d", ctx->prm.n, ctx->batch,
+                  ctx->prm.precision == PISOC_FP64 ? "fp64" : "fp32", ctx->prm.n_classes,
+                  ctx->prm.guess);
+    return b;
+}
+
+bool cache_lookup(const std::string& text, const std::string& key, int* bx, int* cz) {
+    const std::string pat = "\"" + key + "\"";
+    size_t at = text.find(pat);
+    if (at == std::string::npos) return false;
+    at = text.find('[', at + pat.size());
+    if (at == std::string::npos) return false;
+    return std::sscanf(text.c_str() + at, "[%d , %d]", bx, cz) == 2 ||
+           std::sscanf(text.c_str() + at, "[%d,%d]", bx, cz) == 2;
+}
+
+std::string read_file(const char* path) {
+    std::string out;
+    if (!path) return out;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return out;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) out.append(buf, k);
+    std::fclose(f);
+    return out;
+}
+
+// Rewrite the cache with the entry for key replaced or added.
+bool cache_store(const char* path, const std::string& key, int bx, int cz) {
+    std::string text = read_file(path);
+    std::vector<std::pair<std::string, std::pair<int, int>>> entries;
+    size_t pos = 0;
+    for (;;) {
+        const size_t q0 = text.find('"', pos);
+        if (q0 == std::string::npos) break;
+        const size_t q1 = text.find('"', q0 + 1);
+        if (q1 == std::string::npos) break;
+        const std::string k = text.substr(q0 + 1, q1 - q0 - 1);
+        int a, b;
+        if (cache_lookup(text.substr(q0), k, &a, &b) && k != key) entries.push_back({k, {a, b}});
+        pos = text.find(']', q1);
+        if (pos == std::string::npos) break;
+    }
+    entries.push_back({key, {bx, cz}});
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return false;
+    std::fprintf(f, "{\n");
+    for (size_t i = 0; i < entries.size(); ++i)
+        std::fprintf(f, "  \"%s\": [%d, %d]%s\n", entries[i].first.c_str(), entries[i].second.first,
+                     entries[i].second.second, i + 1 < entries.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    return true;
+}
+
+template <typename T>
+void enqueue_probe(pisoc_ctx* ctx) {
+    using O = Ops<T>;
+    StepPtrs<T> S = step_ptrs<T>(ctx);
+    const Phys& ph = ctx->ph;
+    const Launch& L = ctx->L;
+    hipStream_t s = ctx->stream;
+    DevState* st = ctx->st;
+    O::mom_sweep(L, s, ph, st, S.un, S.ua, S.phin, S.aP, S.src, S.pn);
+    O::hbya(L, s, ph, st, S.ua, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0);
+    O::corr_rhs(L, s, ph, st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH, S.r, S.x, S.dg, ctx->part(PS_U),
+                nullptr, nullptr, nullptr, S.b64, S.x64a);
+    // two CG iterations that cannot stop early (tolerance 0, maxit above 2)
+    set_tol(s, st, ctx->batch, 0.0);
+    for (int k = 0; k < 2; ++k) {
+        O::pcg_spmv(L, ctx->TL, s, ph, st, k, S.r, S.dg, S.w, k ? S.pp0 : S.pp1, k ? S.pp1 : S.pp0,
+                    S.q, ctx->part(PS_U), ctx->part(PS_S), 1, 1 << 20);
+        O::pcg_update(L, ctx->TL, s, ph, st, k, S.r, S.q, S.dg, S.x, k ? S.pp1 : S.pp0,
+                      ctx->part(PS_S), ctx->part(PS_U));
+    }
+    if (ctx->prm.n_classes > 0) O::dust_sweep(L, s, ph, st, S.Ya, S.Yb, S.G, S.rj, S.rk);
+}
+
+pisoc_status tune_ctx(pisoc_ctx* ctx, const char* cache_path, int force, int* bx_out, int* cz_out) {
+    const std::string key = tune_key(ctx);
+    int bx = 0, cz = 0;
+    if (!force && cache_lookup(read_file(cache_path), key, &bx, &cz)) {
+        bool ok = false;
+        for (auto [a, b] : shape_candidates(ctx->prm.n)) ok = ok || (a == bx && b == cz);
+        if (ok) {
+            set_shape(ctx, make_launch_shaped(ctx->prm.n, ctx->batch, bx, cz));
+            *bx_out = bx;
+            *cz_out = cz;
+            return PISOC_OK;
+        }
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    const bool prof = ctx->prof.on;
+    ctx->prof.on = false;
+    float best = 1e30f;
+    int best_bx = 0, best_cz = 0;
+    const Launch L0 = ctx->L;
+    for (auto [a, b] : shape_candidates(ctx->prm.n)) {
+        set_shape(ctx, make_launch_shaped(ctx->prm.n, ctx->batch, a, b));
+        auto probe = [&] {
+            if (ctx->prm.precision == PISOC_FP64) enqueue_probe<double>(ctx);
+            else enqueue_probe<float>(ctx);
+        };
+        probe();  // warm-up
+        (void)hipEventRecord(e0, ctx->stream);
+        for (int rep = 0; rep < 3; ++rep) probe();
+        (void)hipEventRecord(e1, ctx->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            best_bx = a;
+            best_cz = b;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->prof.on = prof;
+    HIP_TRY(ctx, hipGetLastError());
+    if (best_bx == 0) {
+        set_shape(ctx, L0);
+        ctx->err = "no launch shape could be timed";
+        return PISOC_ERR_HIP;
+    }
+    set_shape(ctx, make_launch_shaped(ctx->prm.n, ctx->batch, best_bx, best_cz));
+    if (cache_path && !cache_store(cache_path, key, best_bx, best_cz)) {
+        ctx->err = std::string("cannot write ") + cache_path;
+        return PISOC_ERR_INVALID;
+    }
+    *bx_out = best_bx;
+    *cz_out = best_cz;
+    return PISOC_OK;
+}
+
+}  // namespace
+
+// ============================================================ ensemble object
+struct pisoc_ens {
+    int count = 0;
+    std::vector<pisoc_ctx*> cls;                  // one context per grid size
+    std::vector<std::pair<int, int>> where;       // member -> (class, index in class)
+    std::vector<std::vector<int>> members;        // class -> member ids
+    std::vector<hipStream_t> streams;             // one per class (graph branches)
+    hipStream_t stream = nullptr;                 // the ensemble's own stream (capture, replay)
+    hipGraphExec_t exec[2] = {nullptr, nullptr};  // per buffer parity
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
+    int parity = 0;
+    bool built = false;
+    int64_t steps = 0;
+    std::string err;
+};
+
+namespace {
+
+void drop_graphs(pisoc_ens* e) {
+    for (auto& g : e->exec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    e->built = false;
+}
+
+// CG caps of the captured step from the iterations the members needed
+// (margin 25% + 2), and the refinement rounds (one more than needed: the
+// rounds a solve takes vary from step to step by one where the residual after
+// a round lands near the tolerance).
+void set_caps(pisoc_ctx* ctx, const int* first, int later, int rounds) {
+    for (int c = 0; c < ctx->prm.n_corr; ++c)
+        ctx->caps[c] = std::max(ctx->caps[c], (int)std::ceil(1.25 * first[c]) + 2);
+    ctx->cap_later = std::max(ctx->cap_later, (int)std::ceil(1.25 * later) + 2);
+    ctx->rounds = std::max(ctx->rounds, std::max(1, std::min(rounds + 1, ctx->prm.max_refine)));
+}
+
+// Capture one step of every class (fork/join over the class streams) into
+// exec[0], then, with the buffers rotated, into exec[1]; rotations restored.
+pisoc_status build_graphs(pisoc_ens* e) {
+    drop_graphs(e);
+    for (int par = 0; par < 2; ++par) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            e->err = "hipStreamBeginCapture failed";
+            return PISOC_ERR_HIP;
+        }
+        hipError_t rc = hipEventRecord(e->fork, e->stream);
+        pisoc_status st = PISOC_OK;
+        for (size_t c = 0; c < e->cls.size() && rc == hipSuccess && st == PISOC_OK; ++c) {
+            pisoc_ctx* ctx = e->cls[c];
+            rc = hipStreamWaitEvent(ctx->stream, e->fork, 0);
+            if (rc != hipSuccess) break;
+            st = ctx->prm.precision == PISOC_FP64 ? enqueue_step<double>(ctx, false)
+                                                  : enqueue_step<float>(ctx, false);
+            if (st != PISOC_OK) break;
+            rc = hipEventRecord(e->join[c], ctx->stream);
+            if (rc == hipSuccess) rc = hipStreamWaitEvent(e->stream, e->join[c], 0);
+        }
+        const hipError_t rc_end = hipStreamEndCapture(e->stream, &g);
+        if (rc != hipSuccess || st != PISOC_OK || rc_end != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            e->err = std::string("graph capture failed: ") +
+                     hipGetErrorString(rc != hipSuccess ? rc : rc_end);
+            return PISOC_ERR_HIP;
+        }
+        rc = hipGraphInstantiate(&e->exec[par], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (rc != hipSuccess) {
+            e->exec[par] = nullptr;
+            e->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(rc);
+            return PISOC_ERR_HIP;
+        }
+        for (pisoc_ctx* ctx : e->cls) rotate(ctx);
+    }
+    e->built = true;
+    e->parity = 0;
+    return PISOC_OK;
+}
+
+bool same_class_params(const pisoc_params& a, const pisoc_params& b) {
+    return a.n_classes == b.n_classes && a.gamma == b.gamma && a.mu == b.mu && a.cfl == b.cfl &&
+           a.dt_growth == b.dt_growth && a.dt_fixed == b.dt_fixed && a.dt_max == b.dt_max &&
+           a.n_corr == b.n_corr && a.n_mom_sweeps == b.n_mom_sweeps &&
+           a.n_dust_sweeps == b.n_dust_sweeps && a.p_tol == b.p_tol && a.p_maxit == b.p_maxit &&
+           a.precision == b.precision && a.guess == b.guess &&
+           a.d_guess_weights == b.d_guess_weights && a.inner_tol == b.inner_tol &&
+           a.max_refine == b.max_refine && a.capture == b.capture;
+}
+
+// Size classes in order of first appearance; returns false on invalid input.
+bool ens_classes(const pisoc_params* members, int32_t count, std::vector<std::vector<int>>* out,
+                 std::string* why) {
+    out->clear();
+    if (!members || count < 1) {
+        if (why) *why = "no members";
+        return false;
+    }
+    for (int m = 0; m < count; ++m) {
+        if (!valid_params(&members[m], why)) return false;
+        if (!same_class_params(members[m], members[0])) {
+            if (why) *why = "members may differ only in n, C and tau_p";
+            return false;
+        }
+        bool placed = false;
+        for (auto& c : *out)
+            if (members[c[0]].n == members[m].n) {
+                c.push_back(m);
+                placed = true;
+                break;
+            }
+        if (!placed) out->push_back({m});
+    }
+    return true;
+}
+
+std::vector<size_t> ens_offsets(const pisoc_params* members,
+                                const std::vector<std::vector<int>>& classes, size_t* total) {
+    std::vector<size_t> off;
+    size_t o = 0;
+    for (const auto& c : classes) {
+        off.push_back(o);
+        o = align_up(o + make_layout(&members[c[0]], (int)c.size()).total);
+    }
+    *total = o;
+    return off;
+}
+
+// Every class synchronised and its device state copied to the host.
+pisoc_status ens_sync(pisoc_ens* e) {
+    for (pisoc_ctx* ctx : e->cls) {
+        pisoc_status st = sync_state(ctx);
+        if (st != PISOC_OK) {
+            e->err = ctx->err;
+            return st;
+        }
+    }
+    return PISOC_OK;
 }
 
 }  // namespace
@@ -553,7 +1241,7 @@ extern "C" {
 
 size_t pisoc_workspace_bytes(const pisoc_params* prm) {
     if (!valid_params(prm, nullptr)) return 0;
-    return make_layout(prm).total;
+    return make_layout(prm, 1).total;
 }
 
 const char* pisoc_status_string(pisoc_status st) {
@@ -577,82 +1265,18 @@ pisoc_status pisoc_init(const pisoc_params* prm, void* d_workspace, size_t ws_by
     std::string why;
     if (!valid_params(prm, &why)) return PISOC_ERR_INVALID;
     if (!d_rho || !d_u || (prm->n_classes > 0 && !d_rho_p)) return PISOC_ERR_INVALID;
-    Layout lay = make_layout(prm);
+    const Layout lay = make_layout(prm, 1);
     if (!d_workspace || ws_bytes < lay.total ||
         (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
         return PISOC_ERR_WORKSPACE;
-
     pisoc_ctx* ctx = new (std::nothrow) pisoc_ctx();
     if (!ctx) return PISOC_ERR_INVALID;
-    ctx->prm = *prm;
-    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    ctx->ws = reinterpret_cast<char*>(d_workspace);
-    ctx->lay = lay;
-    ctx->L = make_launch(prm->n);
-    ctx->TL = make_tiled_launch(prm->n);
-    // PISOC_UNTILED=1 selects the untiled CG kernel (kernel-comparison tests)
-    if (const char* e = std::getenv("PISOC_UNTILED"); e && e[0] == '1') ctx->TL = Launch{};
-    ctx->st = reinterpret_cast<DevState*>(ctx->ws + lay.state);
-    ctx->partials = reinterpret_cast<double*>(ctx->ws + lay.partials);
-    ctx->u_idx[0] = 0;
-    ctx->u_idx[1] = 1;
-    ctx->u_idx[2] = 2;
-    ctx->rn = lay.rn;
-    ctx->rk = lay.rk;
-    ctx->phin = lay.phin;
-    ctx->phik = lay.phik;
-    ctx->rhop = lay.rhop;
-    ctx->rhop1 = lay.rhop1;
-    ctx->t = 0.0;
-    ctx->dt_prev = __builtin_inf();
-    ctx->steps = 0;
-    ctx->es = prm->precision == PISOC_FP64 ? sizeof(double) : sizeof(float);
-    ctx->prof.reset();
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&ctx->hst), sizeof(DevState),
-                                 hipHostMallocDefault);
-    if (e != hipSuccess) {
-        delete ctx;
-        return PISOC_ERR_HIP;
-    }
-    auto fail = [&](pisoc_status st) {
-        pisoc_destroy(ctx);
+    const pisoc_status st = init_ctx(ctx, prm, 1, reinterpret_cast<char*>(d_workspace), &d_rho,
+                                     &d_u, &d_rho_p, reinterpret_cast<hipStream_t>(hip_stream));
+    if (st != PISOC_OK) {
+        free_ctx(ctx);
         return st;
-    };
-    hipStream_t s = ctx->stream;
-    const size_t N = ctx->N();
-    if (hipMemsetAsync(ctx->st, 0, sizeof(DevState), s) != hipSuccess) return fail(PISOC_ERR_HIP);
-
-    // reference density = mean of the initial density (FP64 reduction of the input)
-    Phys ph0 = make_phys(prm, 1.0);
-    Ops<double>::sum_affine_sq(ctx->L, s, ph0, d_rho, 0.0, 0.0, ctx->part(PS_STAT));
-    finalize_sums(s, ctx->part(PS_STAT), ctx->L.nblocks, 2, ctx->st->red);
-    if (sync_state(ctx) != PISOC_OK) return fail(PISOC_ERR_HIP);
-    const double rho_ref = ctx->hst->red[1] / (double)N;
-    if (!(rho_ref > 0.0) || !std::isfinite(rho_ref)) return fail(PISOC_ERR_INVALID);
-    ctx->ph = make_phys(prm, rho_ref);
-
-    DevState init{};
-    init.pcg.tol2 = prm->p_tol * prm->p_tol;
-    init.pcg.maxit = prm->p_maxit;
-    init.pcg.it_stop = kIterInf;
-    *ctx->hst = init;
-    if (hipMemcpyAsync(ctx->st, ctx->hst, sizeof(DevState), hipMemcpyHostToDevice, s) != hipSuccess)
-        return fail(PISOC_ERR_HIP);
-
-    auto convert = [&](auto tag) {
-        using T = decltype(tag);
-        Ops<T>::cast_in(s, d_rho, ctx->f<T>(ctx->rn), N, rho_ref);
-        Ops<T>::cast_in(s, d_u, ctx->f<T>(lay.u3[0]), 3 * N, 0.0);
-        if (prm->n_classes > 0)
-            Ops<T>::cast_in(s, d_rho_p, ctx->f<T>(ctx->rhop), (size_t)prm->n_classes * N, 0.0);
-        Ops<T>::init_phi(ctx->L, s, ctx->ph, ctx->f<T>(ctx->rn), ctx->f<T>(lay.u3[0]),
-                         ctx->f<T>(ctx->phin));
-    };
-    if (prm->precision == PISOC_FP64) convert(double{});
-    else convert(float{});
-    if (prm->guess == PISOC_GUESS_LEARNED)
-        net_pack_forward(s, reinterpret_cast<const float*>(prm->d_guess_weights), ctx->ws + lay.wpk);
-    if (sync_state(ctx) != PISOC_OK) return fail(PISOC_ERR_HIP);
+    }
     *out = ctx;
     return PISOC_OK;
 }
@@ -661,114 +1285,21 @@ pisoc_status pisoc_step(pisoc_ctx* ctx, int32_t n_steps, pisoc_step_info* h_info
     if (!ctx || n_steps < 0) return PISOC_ERR_INVALID;
     pisoc_status worst = PISOC_OK;
     for (int i = 0; i < n_steps; ++i) {
-        pisoc_status s = ctx->prm.precision == PISOC_FP64
-                             ? one_step<double>(ctx, h_info ? h_info + i : nullptr)
-                             : one_step<float>(ctx, h_info ? h_info + i : nullptr);
+        const pisoc_status s = eager_step(ctx, h_info ? h_info + i : nullptr);
         if (s < 0) return s;
-        if (s > worst) worst = s;
+        worst = combine_status(worst, s);
     }
     return worst;
 }
 
 pisoc_status pisoc_fields(pisoc_ctx* ctx, uint32_t which, double* const* d_dst) {
     if (!ctx || !d_dst) return PISOC_ERR_INVALID;
-    const size_t N = ctx->N();
-    hipStream_t s = ctx->stream;
-    const bool f64 = ctx->prm.precision == PISOC_FP64;
-    int slot = 0;
-    auto cast = [&](size_t off, double* dst, size_t count, double shift) {
-        if (f64) Ops<double>::cast_out(s, ctx->f<double>(off), dst, count, shift);
-        else Ops<float>::cast_out(s, ctx->f<float>(off), dst, count, shift);
-    };
-    const double* snap = ctx->prm.capture ? reinterpret_cast<double*>(ctx->ws + ctx->lay.snap)
-                                          : nullptr;
-    for (int bit = 0; bit < 32; ++bit) {
-        const uint32_t m = 1u << bit;
-        if (!(which & m)) continue;
-        double* dst = d_dst[slot++];
-        if (!dst) return PISOC_ERR_INVALID;
-        switch (m) {
-            case PISOC_FIELD_RHO: cast(ctx->rn, dst, N, ctx->ph.rho_ref); break;
-            case PISOC_FIELD_U: cast(ctx->lay.u3[ctx->u_idx[0]], dst, 3 * N, 0.0); break;
-            case PISOC_FIELD_PHI: cast(ctx->phin, dst, 3 * N, 0.0); break;
-            case PISOC_FIELD_RHO_P:
-                if (ctx->prm.n_classes > 0)
-                    cast(ctx->rhop, dst, (size_t)ctx->prm.n_classes * N, 0.0);
-                break;
-            case PISOC_FIELD_P:
-                if (f64) Ops<double>::pressure_out(s, ctx->ph, ctx->f<double>(ctx->rn), dst);
-                else Ops<float>::pressure_out(s, ctx->ph, ctx->f<float>(ctx->rn), dst);
-                break;
-            case PISOC_FIELD_PSOLVE_B:
-            case PISOC_FIELD_PSOLVE_DIAG:
-            case PISOC_FIELD_P_PREV:
-            case PISOC_FIELD_PSOLVE_X: {
-                if (!snap) {
-                    ctx->err = "captured pressure system requested without params.capture";
-                    return PISOC_ERR_INVALID;
-                }
-                const int idx = m == PISOC_FIELD_PSOLVE_B ? 0
-                                : m == PISOC_FIELD_PSOLVE_DIAG ? 1
-                                : m == PISOC_FIELD_P_PREV ? 2 : 3;
-                HIP_TRY(ctx, hipMemcpyAsync(dst, snap + idx * N, N * sizeof(double),
-                                            hipMemcpyDeviceToDevice, s));
-                break;
-            }
-            default: ctx->err = "unknown field bit"; return PISOC_ERR_INVALID;
-        }
-    }
-    HIP_TRY(ctx, hipGetLastError());
-    return PISOC_OK;
+    return member_fields(ctx, 0, which, d_dst);
 }
 
 pisoc_status pisoc_get_stats(pisoc_ctx* ctx, pisoc_stats* out) {
     if (!ctx || !out) return PISOC_ERR_INVALID;
-    std::memset(out, 0, sizeof(*out));
-    const double N = (double)ctx->N();
-    const Phys& ph = ctx->ph;
-    hipStream_t s = ctx->stream;
-    const bool f64 = ctx->prm.precision == PISOC_FP64;
-    auto gas = [&](auto tag) {
-        using T = decltype(tag);
-        Ops<T>::stats_gas(ctx->L, s, ph, ctx->f<T>(ctx->rn), ctx->f<T>(ctx->lay.u3[ctx->u_idx[0]]),
-                          ctx->part(PS_STAT));
-        finalize_sums(s, ctx->part(PS_STAT), ctx->L.nblocks, 4, ctx->st->red);
-    };
-    auto affine = [&](auto tag, size_t off, double a, double b) {
-        using T = decltype(tag);
-        Ops<T>::sum_affine_sq(ctx->L, s, ph, ctx->f<T>(off), a, b, ctx->part(PS_STAT));
-        finalize_sums(s, ctx->part(PS_STAT), ctx->L.nblocks, 2, ctx->st->red + 4);
-    };
-    if (f64) gas(double{}); else gas(float{});
-    pisoc_status st = sync_state(ctx);
-    if (st != PISOC_OK) return st;
-    const double ke = ctx->hst->red[0], ens = ctx->hst->red[1], usq = ctx->hst->red[2],
-                 rsum = ctx->hst->red[3];
-    const double rbar = rsum / N;
-    if (f64) affine(double{}, ctx->rn, 1.0, -rbar); else affine(float{}, ctx->rn, 1.0, -rbar);
-    if ((st = sync_state(ctx)) != PISOC_OK) return st;
-    const double rvar = ctx->hst->red[4];
-    const double rmean = ph.rho_ref + rbar;
-    out->ke = ke / N;
-    out->enstrophy = ens / N;
-    out->rho_rms = std::sqrt(rvar / N) / rmean;
-    const double c0 = std::sqrt(ph.gamma * ph.C * std::pow(rmean, ph.gamma - 1.0));
-    out->mach_rms = std::sqrt(usq / N) / c0;
-    out->mass_gas = rmean * N * ph.V;
-    const size_t Nc = ctx->N();
-    for (int c = 0; c < ctx->prm.n_classes; ++c) {
-        const size_t off = ctx->rhop + (f64 ? sizeof(double) : sizeof(float)) * Nc * c;
-        if (f64) affine(double{}, off, 0.0, 0.0); else affine(float{}, off, 0.0, 0.0);
-        if ((st = sync_state(ctx)) != PISOC_OK) return st;
-        const double m = ctx->hst->red[5] / N;
-        if (m != 0.0) {
-            if (f64) affine(double{}, off, 1.0 / m, -1.0); else affine(float{}, off, 1.0 / m, -1.0);
-            if ((st = sync_state(ctx)) != PISOC_OK) return st;
-            out->conc_var[c] = ctx->hst->red[4] / N;
-        }
-        out->mass_p[c] = m * N * ph.V;
-    }
-    return PISOC_OK;
+    return all_stats(ctx, out);
 }
 
 pisoc_status pisoc_profile(pisoc_ctx* ctx, int32_t enable) {
@@ -790,20 +1321,307 @@ int32_t pisoc_profile_read(const pisoc_ctx* ctx, pisoc_kernel_stat* out, int32_t
 double pisoc_time(const pisoc_ctx* ctx) { return ctx ? ctx->t : 0.0; }
 int64_t pisoc_steps_done(const pisoc_ctx* ctx) { return ctx ? ctx->steps : 0; }
 
-void pisoc_destroy(pisoc_ctx* ctx) {
-    if (!ctx) return;
-    if (ctx->hst) (void)hipHostFree(ctx->hst);
-    delete ctx;
-}
+void pisoc_destroy(pisoc_ctx* ctx) { free_ctx(ctx); }
 
 const char* pisoc_last_error(const pisoc_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+// ---------------------------------------------------------------- ensembles
+size_t pisoc_ens_workspace_bytes(const pisoc_params* members, int32_t count) {
+    std::vector<std::vector<int>> classes;
+    if (!ens_classes(members, count, &classes, nullptr)) return 0;
+    size_t total = 0;
+    (void)ens_offsets(members, classes, &total);
+    return total;
+}
+
+pisoc_status pisoc_ens_init(const pisoc_params* members, int32_t count, void* d_workspace,
+                            size_t ws_bytes, const double* const* d_rho, const double* const* d_u,
+                            const double* const* d_rho_p, void* hip_stream, pisoc_ens** out) {
+    if (!out) return PISOC_ERR_INVALID;
+    *out = nullptr;
+    std::vector<std::vector<int>> classes;
+    if (!ens_classes(members, count, &classes, nullptr) || !d_rho || !d_u) return PISOC_ERR_INVALID;
+    for (int m = 0; m < count; ++m)
+        if (!d_rho[m] || !d_u[m] || (members[m].n_classes > 0 && (!d_rho_p || !d_rho_p[m])))
+            return PISOC_ERR_INVALID;
+    size_t total = 0;
+    const std::vector<size_t> off = ens_offsets(members, classes, &total);
+    if (!d_workspace || ws_bytes < total || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
+        return PISOC_ERR_WORKSPACE;
+    pisoc_ens* e = new (std::nothrow) pisoc_ens();
+    if (!e) return PISOC_ERR_INVALID;
+    e->count = count;
+    e->members = classes;
+    e->where.assign(count, {0, 0});
+    pisoc_status st = PISOC_OK;
+    if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess) {
+        e->stream = nullptr;
+        st = PISOC_ERR_HIP;
+    }
+    if (st == PISOC_OK && hipEventCreateWithFlags(&e->fork, hipEventDisableTiming) != hipSuccess)
+        st = PISOC_ERR_HIP;
+    // class streams wait for the caller's stream (the inputs) before the set-up
+    hipEvent_t ready = nullptr;
+    if (st == PISOC_OK &&
+        (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+         hipEventRecord(ready, reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess))
+        st = PISOC_ERR_HIP;
+    for (size_t c = 0; c < classes.size() && st == PISOC_OK; ++c) {
+        hipStream_t s = nullptr;
+        hipEvent_t j = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            st = PISOC_ERR_HIP;
+            break;
+        }
+        e->streams.push_back(s);
+        if (hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+            st = PISOC_ERR_HIP;
+            break;
+        }
+        e->join.push_back(j);
+        if (hipStreamWaitEvent(s, ready, 0) != hipSuccess) {
+            st = PISOC_ERR_HIP;
+            break;
+        }
+        std::vector<pisoc_params> mp;
+        std::vector<const double*> r, u, rp;
+        for (size_t i = 0; i < classes[c].size(); ++i) {
+            const int m = classes[c][i];
+            e->where[m] = {(int)c, (int)i};
+            mp.push_back(members[m]);
+            r.push_back(d_rho[m]);
+            u.push_back(d_u[m]);
+            rp.push_back(d_rho_p ? d_rho_p[m] : nullptr);
+        }
+        pisoc_ctx* ctx = new (std::nothrow) pisoc_ctx();
+        if (!ctx) {
+            st = PISOC_ERR_INVALID;
+            break;
+        }
+        e->cls.push_back(ctx);
+        st = init_ctx(ctx, mp.data(), (int)mp.size(), reinterpret_cast<char*>(d_workspace) + off[c],
+                      r.data(), u.data(), rp.data(), s);
+        if (st != PISOC_OK) e->err = ctx->err;
+    }
+    if (ready) (void)hipEventDestroy(ready);
+    if (st != PISOC_OK) {
+        pisoc_ens_destroy(e);
+        return st;
+    }
+    *out = e;
+    return PISOC_OK;
+}
+
+pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_step_info* h_info) {
+    if (!e || n_steps < 0 || (mode != PISOC_ENS_EAGER && mode != PISOC_ENS_GRAPH))
+        return PISOC_ERR_INVALID;
+    if (n_steps == 0) return PISOC_OK;
+    pisoc_status worst = PISOC_OK;
+    std::vector<pisoc_step_info> rec(e->count);
+    if (mode == PISOC_ENS_EAGER || !e->built) {
+        // eager steps (the first captured call begins with one: it measures
+        // the CG iterations that size the graph's caps)
+        const int k = mode == PISOC_ENS_EAGER ? n_steps : 1;
+        for (int i = 0; i < k; ++i) {
+            for (size_t c = 0; c < e->cls.size(); ++c) {
+                pisoc_ctx* ctx = e->cls[c];
+                std::vector<pisoc_step_info> ci(ctx->batch);
+                const pisoc_status s = eager_step(ctx, ci.data());
+                if (s < 0) {
+                    e->err = ctx->err;
+                    return s;
+                }
+                worst = combine_status(worst, s);
+                for (int j = 0; j < ctx->batch; ++j) rec[e->members[c][j]] = ci[j];
+                // iterations for the caps of the captured step
+                int first[PISOC_MAX_CORR] = {0, 0, 0, 0};
+                int later = 0, rounds = 1;
+                for (int j = 0; j < ctx->batch; ++j) {
+                    const DevState& h = ctx->hst[j];
+                    for (int q = 0; q < ctx->prm.n_corr; ++q) {
+                        first[q] = std::max(first[q], h.it_first[q]);
+                        rounds = std::max(rounds, h.rounds_corr[q]);
+                    }
+                    for (int q = 0; q < ctx->prm.n_corr; ++q) later = std::max(later, h.it_later[q]);
+                }
+                set_caps(ctx, first, later, rounds);
+            }
+            e->steps += 1;
+        }
+        if (mode == PISOC_ENS_EAGER) {
+            if (h_info) std::copy(rec.begin(), rec.end(), h_info);
+            return worst;
+        }
+        n_steps -= 1;
+        pisoc_status st = build_graphs(e);
+        if (st != PISOC_OK) return st;
+    }
+    if (n_steps > 0) {
+        // the graph runs on the ensemble's stream: earlier work on the class
+        // streams (set-up, eager steps, copies) must be complete
+        for (pisoc_ctx* ctx : e->cls)
+            if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+                e->err = "stream synchronisation failed";
+                return PISOC_ERR_HIP;
+            }
+        for (pisoc_ctx* ctx : e->cls) clear_acc(e->stream, ctx->st, ctx->batch);
+        for (int i = 0; i < n_steps; ++i) {
+            const hipError_t rc = hipGraphLaunch(e->exec[e->parity], e->stream);
+            if (rc != hipSuccess) {
+                e->err = std::string("hipGraphLaunch: ") + hipGetErrorString(rc);
+                return PISOC_ERR_HIP;
+            }
+            e->parity ^= 1;
+            for (pisoc_ctx* ctx : e->cls) {
+                rotate(ctx);
+                ctx->steps += 1;
+            }
+            e->steps += 1;
+        }
+        if (hipStreamSynchronize(e->stream) != hipSuccess) {
+            e->err = "stream synchronisation failed";
+            return PISOC_ERR_HIP;
+        }
+        pisoc_status st = ens_sync(e);
+        if (st != PISOC_OK) return st;
+        bool regrow_any = false, bad = false, bad_dt = false;
+        for (size_t c = 0; c < e->cls.size(); ++c) {
+            pisoc_ctx* ctx = e->cls[c];
+            int first[PISOC_MAX_CORR] = {0, 0, 0, 0};
+            int later = 0;
+            bool regrow = false;
+            for (int j = 0; j < ctx->batch; ++j) {
+                const DevState& h = ctx->hst[j];
+                fill_info(ctx, h, true, &rec[e->members[c][j]]);
+                rec[e->members[c][j]].flags |= h.flags_acc;
+                worst = combine_status(worst, flag_status(h.flags_acc));
+                if (member_bad(ctx, h) || (h.flags_acc & (PISOC_FLAG_NONFINITE | PISOC_FLAG_RHO_NONPOS)))
+                    bad = true;
+                for (int q = 0; q < ctx->prm.n_corr; ++q) first[q] = std::max(first[q], h.it_first_max[q]);
+                for (int q = 0; q < ctx->prm.n_corr; ++q) later = std::max(later, h.it_later_max[q]);
+                if (h.flags_acc & PISOC_FLAG_PCG_MAXIT) regrow = true;
+                if (h.flags_acc & PISOC_FLAG_BAD_DT) bad_dt = true;
+            }
+            if (regrow) {
+                // a solve hit its cap: grow the caps by half and re-capture
+                for (int q = 0; q < ctx->prm.n_corr; ++q)
+                    if (first[q] >= ctx->caps[q]) ctx->caps[q] = ctx->caps[q] * 3 / 2 + 2;
+                if (later >= ctx->cap_later) ctx->cap_later = ctx->cap_later * 3 / 2 + 2;
+                ctx->rounds = std::min(ctx->prm.max_refine, ctx->rounds + 1);
+            }
+            set_caps(ctx, first, later, ctx->rounds - 1);
+            regrow_any = regrow_any || regrow;
+        }
+        if (regrow_any) drop_graphs(e);
+        if (bad_dt) {
+            e->err = "time step undefined or non-positive in a member";
+            if (h_info) std::copy(rec.begin(), rec.end(), h_info);
+            return PISOC_ERR_INVALID;
+        }
+        if (bad) {
+            e->err = "a member diverged (non-finite field or non-positive density)";
+            if (h_info) std::copy(rec.begin(), rec.end(), h_info);
+            return PISOC_ERR_DIVERGED;
+        }
+    }
+    if (h_info) std::copy(rec.begin(), rec.end(), h_info);
+    return worst;
+}
+
+pisoc_status pisoc_ens_fields(pisoc_ens* e, int32_t member, uint32_t which, double* const* d_dst) {
+    if (!e || member < 0 || member >= e->count || !d_dst) return PISOC_ERR_INVALID;
+    const auto [c, i] = e->where[member];
+    const pisoc_status st = member_fields(e->cls[c], i, which, d_dst);
+    if (st != PISOC_OK) e->err = e->cls[c]->err;
+    return st;
+}
+
+pisoc_status pisoc_ens_get_stats(pisoc_ens* e, pisoc_stats* h_out) {
+    if (!e || !h_out) return PISOC_ERR_INVALID;
+    for (size_t c = 0; c < e->cls.size(); ++c) {
+        std::vector<pisoc_stats> s(e->cls[c]->batch);
+        const pisoc_status st = all_stats(e->cls[c], s.data());
+        if (st != PISOC_OK) {
+            e->err = e->cls[c]->err;
+            return st;
+        }
+        for (size_t i = 0; i < s.size(); ++i) h_out[e->members[c][i]] = s[i];
+    }
+    return PISOC_OK;
+}
+
+pisoc_status pisoc_ens_time(pisoc_ens* e, double* h_t) {
+    if (!e || !h_t) return PISOC_ERR_INVALID;
+    pisoc_status st = ens_sync(e);
+    if (st != PISOC_OK) return st;
+    for (int m = 0; m < e->count; ++m) {
+        const auto [c, i] = e->where[m];
+        h_t[m] = e->cls[c]->hst[i].t;
+    }
+    return PISOC_OK;
+}
+
+int64_t pisoc_ens_steps_done(const pisoc_ens* e) { return e ? e->steps : 0; }
+
+int32_t pisoc_ens_num_classes(const pisoc_ens* e) { return e ? (int32_t)e->cls.size() : 0; }
+
+pisoc_status pisoc_ens_class_info(const pisoc_ens* e, int32_t cls, pisoc_ens_class* h_out) {
+    if (!e || !h_out || cls < 0 || cls >= (int32_t)e->cls.size()) return PISOC_ERR_INVALID;
+    const pisoc_ctx* ctx = e->cls[cls];
+    pisoc_ens_class o{};
+    o.n = ctx->prm.n;
+    o.members = ctx->batch;
+    o.block_x = (int32_t)ctx->L.block.x;
+    o.block_y = (int32_t)ctx->L.block.y;
+    o.cells_z = ctx->L.cz;
+    o.blocks = (int32_t)ctx->L.nblocks;
+    o.rounds = ctx->rounds;
+    o.cap_later = ctx->cap_later;
+    for (int c = 0; c < PISOC_MAX_CORR; ++c) o.caps[c] = ctx->caps[c];
+    *h_out = o;
+    return PISOC_OK;
+}
+
+pisoc_status pisoc_ens_autotune(pisoc_ens* e, const char* cache_path, int32_t force) {
+    if (!e) return PISOC_ERR_INVALID;
+    if (e->steps < 1) {
+        e->err = "autotune needs one completed step (the timed kernels run on its systems)";
+        return PISOC_ERR_INVALID;
+    }
+    pisoc_status st = ens_sync(e);
+    if (st != PISOC_OK) return st;
+    for (pisoc_ctx* ctx : e->cls) {
+        int bx = 0, cz = 0;
+        st = tune_ctx(ctx, cache_path, force, &bx, &cz);
+        if (st != PISOC_OK) {
+            e->err = ctx->err;
+            return st;
+        }
+    }
+    drop_graphs(e);
+    return ens_sync(e);
+}
+
+void pisoc_ens_destroy(pisoc_ens* e) {
+    if (!e) return;
+    for (pisoc_ctx* ctx : e->cls)
+        if (ctx && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    drop_graphs(e);
+    for (pisoc_ctx* ctx : e->cls) free_ctx(ctx);
+    for (hipStream_t s : e->streams) (void)hipStreamDestroy(s);
+    for (hipEvent_t j : e->join) (void)hipEventDestroy(j);
+    if (e->fork) (void)hipEventDestroy(e->fork);
+    if (e->stream) (void)hipStreamDestroy(e->stream);
+    delete e;
+}
+
+const char* pisoc_ens_last_error(const pisoc_ens* e) { return e ? e->err.c_str() : ""; }
 
 // ---------------------------------------------------------------- Helmholtz
 static Layout helm_layout(int32_t n) {
     Layout L{};
     const size_t N = (size_t)n * n * n;
-    const Launch lc = make_launch(n);
-    L.max_blocks = std::max(lc.nblocks, make_tiled_launch(n).nblocks);
+    L.max_blocks = std::max(make_launch(n, 1).nblocks, make_tiled_launch(n, 1).nblocks);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     L.state = take(sizeof(DevState));
@@ -817,6 +1635,14 @@ static Layout helm_layout(int32_t n) {
     return L;
 }
 
+static pisoc_params plain_params(int32_t n) {
+    pisoc_params p{};
+    p.n = n;
+    p.gamma = 1.4;
+    p.C = 1.0;
+    return p;
+}
+
 size_t pisoc_helm_workspace_bytes(int32_t n) {
     if (n < PISOC_MIN_N || n > PISOC_MAX_N) return 0;
     return helm_layout(n).total;
@@ -826,12 +1652,9 @@ pisoc_status pisoc_helm_apply(int32_t n, const double* d_psidt, const double* d_
                               const double* d_x, double* d_y, void* hip_stream) {
     if (n < PISOC_MIN_N || n > PISOC_MAX_N || !d_psidt || !d_w || !d_x || !d_y)
         return PISOC_ERR_INVALID;
-    pisoc_params p{};
-    p.n = n;
-    p.gamma = 1.4;
-    p.C = 1.0;
-    Phys ph = make_phys(&p, 1.0);
-    Launch L = make_launch(n);
+    const pisoc_params p = plain_params(n);
+    const Launch L = make_launch(n, 1);
+    const Phys ph = make_phys(&p, L, 1);
     Ops<double>::helm_apply(L, reinterpret_cast<hipStream_t>(hip_stream), ph, d_psidt, d_w, d_x, d_y);
     return hipGetLastError() == hipSuccess ? PISOC_OK : PISOC_ERR_HIP;
 }
@@ -843,28 +1666,31 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
     if (n < PISOC_MIN_N || n > PISOC_MAX_N || !d_psidt || !d_w || !d_b || !d_x ||
         !(tol > 0.0) || !(tol < 1.0) || maxit < 1)
         return PISOC_ERR_INVALID;
-    Layout lay = helm_layout(n);
+    const Layout lay = helm_layout(n);
     if (!d_workspace || ws_bytes < lay.total ||
         (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
         return PISOC_ERR_WORKSPACE;
     pisoc_ctx ctx{};
-    ctx.prm.n = n;
+    ctx.prm = plain_params(n);
     ctx.prm.p_maxit = maxit;
-    ctx.prm.gamma = 1.4;
-    ctx.prm.C = 1.0;
+    ctx.batch = 1;
     ctx.stream = reinterpret_cast<hipStream_t>(hip_stream);
     ctx.ws = reinterpret_cast<char*>(d_workspace);
     ctx.lay = lay;
-    ctx.ph = make_phys(&ctx.prm, 1.0);
-    ctx.L = make_launch(n);
-    ctx.TL = make_tiled_launch(n);
+    ctx.L = make_launch(n, 1);
+    ctx.TL = make_tiled_launch(n, 1);
+    ctx.ph = make_phys(&ctx.prm, ctx.L, 1);
+    ctx.es = sizeof(double);
     ctx.st = reinterpret_cast<DevState*>(ctx.ws + lay.state);
     ctx.partials = reinterpret_cast<double*>(ctx.ws + lay.partials);
     if (hipHostMalloc(reinterpret_cast<void**>(&ctx.hst), sizeof(DevState), hipHostMallocDefault) !=
-        hipSuccess)
+        hipSuccess) {
+        ctx.hst = nullptr;
         return PISOC_ERR_HIP;
+    }
     DevState init{};
     init.pcg.tol2 = tol * tol;
+    init.pcg.tol_final = tol * tol;
     init.pcg.maxit = maxit;
     init.pcg.it_stop = kIterInf;
     *ctx.hst = init;
@@ -877,16 +1703,13 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
         double* dg = ctx.f<double>(lay.diag);
         Ops<double>::helm_start(ctx.L, ctx.stream, ctx.ph, ctx.st, d_psidt, d_w, d_b, d_x, r, dg,
                                 ctx.part(PS_U));
-        int32_t it = 0;
-        double rel = 0.0;
-        bool conv = false;
         st = run_pcg<double>(&ctx, r, d_x, dg, const_cast<double*>(d_w), ctx.f<double>(lay.pp0),
-                             ctx.f<double>(lay.pp1), ctx.f<double>(lay.q), tol, 16, &it, &rel,
-                             &conv);
+                             ctx.f<double>(lay.pp1), ctx.f<double>(lay.q), true, 16, true, nullptr);
         if (st == PISOC_OK) {
-            if (iters) *iters = it;
-            if (relres) *relres = rel;
-            if (!conv) st = PISOC_WARN_NOT_CONVERGED;
+            const PcgState& g = ctx.hst->pcg;
+            if (iters) *iters = g.iters;
+            if (relres) *relres = g.bb > 0.0 ? std::sqrt(g.rr / g.bb) : 0.0;
+            if (!g.converged) st = PISOC_WARN_NOT_CONVERGED;
         }
     }
     (void)hipHostFree(ctx.hst);
@@ -901,16 +1724,13 @@ pisoc_status pisoc_net_inputs(int32_t n, const double* d_b, const double* d_diag
     if (n < PISOC_MIN_N || n > PISOC_MAX_N || !d_b || !d_diag || !d_p0 || !d_x ||
         (d_t && !d_psol))
         return PISOC_ERR_INVALID;
-    Layout lay = helm_layout(n);
+    const Layout lay = helm_layout(n);
     if (!d_workspace || ws_bytes < lay.total ||
         (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
         return PISOC_ERR_WORKSPACE;
-    pisoc_params p{};
-    p.n = n;
-    p.gamma = 1.4;
-    p.C = 1.0;
-    Phys ph = make_phys(&p, 1.0);
-    Launch L = make_launch(n);
+    const pisoc_params p = plain_params(n);
+    const Launch L = make_launch(n, 1);
+    const Phys ph = make_phys(&p, L, 1);
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     char* ws = reinterpret_cast<char*>(d_workspace);
     DevState* st = reinterpret_cast<DevState*>(ws + lay.state);

@@ -156,6 +156,24 @@ def make_hit_case(n: int, seed: int, mach: float = 0.2, stokes=(0.1,), gamma: fl
                    rho=rho, u=np.ascontiguousarray(u), rho_p=np.ascontiguousarray(rho_p))
 
 
+def ensemble_cases(count: int = 64, seed: int = 0, sizes=(32, 32, 48, 64),
+                   machs=(0.2, 0.5), stokes_range=(0.05, 0.5)):
+    """Members of a mixed-size ensemble of decaying-HIT realisations.
+
+    Member m has grid size ``sizes[m % len(sizes)]`` (the default gives 32^3,
+    48^3 and 64^3 in the ratio 2:1:1), flow seed ``seed + m``, an r.m.s. Mach
+    number drawn from ``machs`` and one particle class whose Stokes number is
+    drawn uniformly from ``stokes_range``; both draws come from a generator
+    seeded with ``seed``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for m in range(count):
+        mach = float(machs[int(rng.integers(len(machs)))])
+        st = float(rng.uniform(*stokes_range))
+        out.append(make_hit_case(sizes[m % len(sizes)], seed + m, mach=mach, stokes=(st,)))
+    return out
+
+
 def run_name(n: int, mach: float, stokes, seed: int, scheme: str = "PISO", sgs: str = "noM") -> str:
     """Run name in the paper's scheme.subgrid-model.<...>.cells-per-side pattern,
     extended with Mach, Stokes numbers and seed, e.g. ``PISO.noM.32.Ma02.St0.1.s0``."""

@@ -11,12 +11,25 @@ tensors); every arithmetic step runs in the HIP library.
 from __future__ import annotations
 
 import math
+import os
 import time
 
 import numpy as np
 
 from . import pisoc as P
 from .inputs import make_hit_case
+
+
+WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                            "guess_hit32.npy")
+
+
+def load_weights(path: str = WEIGHTS_PATH, device="cuda:0"):
+    """The trained FP32 weights as a device tensor (numpy load, no pickle)."""
+    import torch
+    w = np.load(path, allow_pickle=False).astype(np.float32)
+    assert w.shape == (P.NET_NWEIGHTS,), w.shape
+    return torch.as_tensor(w, device=device).contiguous()
 
 
 def init_weights(seed: int = 0):

@@ -32,7 +32,11 @@ EXPORTED = [
     "pisoc_profile", "pisoc_profile_read",
     "pisoc_net_workspace_bytes", "pisoc_net_forward", "pisoc_net_grad", "pisoc_net_adam",
     "pisoc_net_inputs",
+    "pisoc_ens_workspace_bytes", "pisoc_ens_init", "pisoc_ens_step", "pisoc_ens_fields",
+    "pisoc_ens_get_stats", "pisoc_ens_time", "pisoc_ens_steps_done", "pisoc_ens_num_classes",
+    "pisoc_ens_class_info", "pisoc_ens_autotune", "pisoc_ens_destroy", "pisoc_ens_last_error",
 ]
+ENS_EAGER, ENS_GRAPH = 0, 1
 NET_NWEIGHTS = 15120
 NET_CH = (2, 16, 16, 16, 1)
 
@@ -71,6 +75,12 @@ class Stats(C.Structure):
         ("mach_rms", C.c_double), ("mass_gas", C.c_double),
         ("conc_var", C.c_double * MAX_CLASSES), ("mass_p", C.c_double * MAX_CLASSES),
     ]
+
+
+class EnsClass(C.Structure):
+    _fields_ = [("n", C.c_int32), ("members", C.c_int32), ("block_x", C.c_int32),
+                ("block_y", C.c_int32), ("cells_z", C.c_int32), ("blocks", C.c_int32),
+                ("caps", C.c_int32 * MAX_CORR), ("cap_later", C.c_int32), ("rounds", C.c_int32)]
 
 
 class KernelStat(C.Structure):
@@ -134,6 +144,31 @@ def lib():
     L.pisoc_net_adam.restype = C.c_int
     L.pisoc_net_inputs.argtypes = [i32, vp, vp, vp, vp, fp, fp, C.POINTER(f64), vp, sz, vp]
     L.pisoc_net_inputs.restype = C.c_int
+    pp = C.POINTER(vp)
+    L.pisoc_ens_workspace_bytes.argtypes = [C.POINTER(Params), i32]
+    L.pisoc_ens_workspace_bytes.restype = sz
+    L.pisoc_ens_init.argtypes = [C.POINTER(Params), i32, vp, sz, pp, pp, pp, vp, C.POINTER(vp)]
+    L.pisoc_ens_init.restype = C.c_int
+    L.pisoc_ens_step.argtypes = [vp, i32, i32, C.POINTER(StepInfo)]
+    L.pisoc_ens_step.restype = C.c_int
+    L.pisoc_ens_fields.argtypes = [vp, i32, C.c_uint32, pp]
+    L.pisoc_ens_fields.restype = C.c_int
+    L.pisoc_ens_get_stats.argtypes = [vp, C.POINTER(Stats)]
+    L.pisoc_ens_get_stats.restype = C.c_int
+    L.pisoc_ens_time.argtypes = [vp, C.POINTER(f64)]
+    L.pisoc_ens_time.restype = C.c_int
+    L.pisoc_ens_steps_done.argtypes = [vp]
+    L.pisoc_ens_steps_done.restype = C.c_int64
+    L.pisoc_ens_num_classes.argtypes = [vp]
+    L.pisoc_ens_num_classes.restype = i32
+    L.pisoc_ens_class_info.argtypes = [vp, i32, C.POINTER(EnsClass)]
+    L.pisoc_ens_class_info.restype = C.c_int
+    L.pisoc_ens_autotune.argtypes = [vp, C.c_char_p, i32]
+    L.pisoc_ens_autotune.restype = C.c_int
+    L.pisoc_ens_destroy.argtypes = [vp]
+    L.pisoc_ens_destroy.restype = None
+    L.pisoc_ens_last_error.argtypes = [vp]
+    L.pisoc_ens_last_error.restype = C.c_char_p
     _lib = L
     return L
 
@@ -228,19 +263,13 @@ class Solver:
 
     def step(self, n_steps=1, raise_on_error=True):
         infos = (StepInfo * max(n_steps, 1))()
+        before = lib().pisoc_steps_done(self._h)
         st = lib().pisoc_step(self._h, n_steps, infos)
         if st < 0 and raise_on_error:
             raise PisocError(st, self.last_error())
         nc = self.prm.n_corr
-        done = n_steps if st >= 0 else None
-        out = []
-        for i in range(n_steps if done is None else done):
-            r = infos[i]
-            out.append(dict(t=r.t, dt=r.dt, courant=r.courant,
-                            pcg_iters=list(r.pcg_iters[:nc]), pcg_relres=list(r.pcg_relres[:nc]),
-                            refinements=list(r.refinements[:nc]), flags=r.flags,
-                            mass_gas=r.mass_gas, mass_p=list(r.mass_p[: self.K])))
-        return st, out
+        done = n_steps if st >= 0 else lib().pisoc_steps_done(self._h) - before
+        return st, [_info_dict(infos[i], nc, self.K) for i in range(done)]
 
     def fields(self, which):
         """Return {bit: float64 tensor} for the requested field bits."""
@@ -290,6 +319,138 @@ class Solver:
         n = lib().pisoc_profile_read(self._h, arr, MAX_KSTATS)
         return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms,
                                            bytes=arr[i].bytes) for i in range(n)}
+
+
+def _info_dict(r, nc, K):
+    return dict(t=r.t, dt=r.dt, courant=r.courant, pcg_iters=list(r.pcg_iters[:nc]),
+                pcg_relres=list(r.pcg_relres[:nc]), refinements=list(r.refinements[:nc]),
+                flags=r.flags, mass_gas=r.mass_gas, mass_p=list(r.mass_p[:K]))
+
+
+class Ensemble:
+    """Independent members (mixed grid sizes) stepped together on one GPU.
+
+    ``cases``: objects with n, rho, u, rho_p, gamma, C, mu, tau_p (as made by
+    ``inputs.make_hit_case``); ``kw``: the parameters every member shares."""
+
+    def __init__(self, cases, *, device="cuda:0", **kw):
+        torch = _torch()
+        self.torch, self.device = torch, torch.device(device)
+        self.count = len(cases)
+        prms = (Params * self.count)()
+        keep = []
+        for m, c in enumerate(cases):
+            prms[m] = make_params(c.n, gamma=c.gamma, C_=c.C, mu=c.mu, tau_p=c.tau_p, **kw)
+        self.prms = prms
+        self.ns = [c.n for c in cases]
+        self.K = prms[0].n_classes
+        L = lib()
+        nbytes = L.pisoc_ens_workspace_bytes(prms, self.count)
+        if nbytes == 0:
+            raise PisocError(ERR_INVALID, "invalid ensemble parameters")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        arrs = [[], [], []]
+        for c in cases:
+            r = torch.as_tensor(c.rho, dtype=torch.float64, device=self.device).contiguous()
+            u = torch.as_tensor(c.u, dtype=torch.float64, device=self.device).contiguous()
+            keep += [r, u]
+            arrs[0].append(r.data_ptr())
+            arrs[1].append(u.data_ptr())
+            if self.K:
+                rp = torch.as_tensor(c.rho_p, dtype=torch.float64, device=self.device).contiguous()
+                keep.append(rp)
+                arrs[2].append(rp.data_ptr())
+            else:
+                arrs[2].append(None)
+        ptrs = [(C.c_void_p * self.count)(*a) for a in arrs]
+        h = C.c_void_p()
+        st = L.pisoc_ens_init(prms, self.count, self.ws.data_ptr(), nbytes, ptrs[0], ptrs[1],
+                              ptrs[2] if self.K else None,
+                              _stream_ptr(torch, None), C.byref(h))
+        if st != OK:
+            raise PisocError(st, "pisoc_ens_init failed")
+        self._h = h
+        del keep
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.pisoc_ens_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def last_error(self) -> str:
+        return lib().pisoc_ens_last_error(self._h).decode()
+
+    def step(self, n_steps=1, mode=ENS_GRAPH, raise_on_error=True):
+        """Advance every member; returns (status, [last-step record per member])."""
+        infos = (StepInfo * self.count)()
+        st = lib().pisoc_ens_step(self._h, n_steps, mode, infos)
+        if st < 0 and raise_on_error:
+            raise PisocError(st, self.last_error())
+        nc = self.prms[0].n_corr
+        return st, [_info_dict(infos[m], nc, self.K) for m in range(self.count)]
+
+    def autotune(self, cache_path=None, force=False):
+        st = lib().pisoc_ens_autotune(self._h, cache_path.encode() if cache_path else None,
+                                      1 if force else 0)
+        if st != OK:
+            raise PisocError(st, self.last_error())
+
+    def classes(self):
+        out = []
+        for c in range(lib().pisoc_ens_num_classes(self._h)):
+            e = EnsClass()
+            st = lib().pisoc_ens_class_info(self._h, c, C.byref(e))
+            if st != OK:
+                raise PisocError(st, self.last_error())
+            out.append(dict(n=e.n, members=e.members, block=(e.block_x, e.block_y),
+                            cells_z=e.cells_z, blocks=e.blocks, caps=list(e.caps),
+                            cap_later=e.cap_later, rounds=e.rounds))
+        return out
+
+    def fields(self, m, which):
+        torch = self.torch
+        n = self.ns[m]
+        shapes = {FIELD_RHO: (n, n, n), FIELD_U: (3, n, n, n), FIELD_PHI: (3, n, n, n),
+                  FIELD_RHO_P: (max(self.K, 1), n, n, n), FIELD_P: (n, n, n)}
+        bits = [b for b in sorted(shapes) if which & b]
+        outs = [torch.empty(shapes[b], dtype=torch.float64, device=self.device) for b in bits]
+        arr = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        st = lib().pisoc_ens_fields(self._h, m, which, arr)
+        if st != OK:
+            raise PisocError(st, self.last_error())
+        torch.cuda.synchronize(self.device)
+        res = dict(zip(bits, outs))
+        if FIELD_RHO_P in res:
+            res[FIELD_RHO_P] = res[FIELD_RHO_P][: self.K]
+        return res
+
+    def get(self, m, bit):
+        return self.fields(m, bit)[bit]
+
+    def stats(self):
+        arr = (Stats * self.count)()
+        st = lib().pisoc_ens_get_stats(self._h, arr)
+        if st != OK:
+            raise PisocError(st, self.last_error())
+        K = self.K
+        return [dict(ke=s.ke, enstrophy=s.enstrophy, rho_rms=s.rho_rms, mach_rms=s.mach_rms,
+                     mass_gas=s.mass_gas, conc_var=list(s.conc_var[:K]), mass_p=list(s.mass_p[:K]))
+                for s in arr]
+
+    def times(self):
+        arr = (C.c_double * self.count)()
+        st = lib().pisoc_ens_time(self._h, arr)
+        if st != OK:
+            raise PisocError(st, self.last_error())
+        return list(arr)
+
+    @property
+    def steps_done(self):
+        return lib().pisoc_ens_steps_done(self._h)
 
 
 class Net:

@@ -1,0 +1,180 @@
+"""The batched ensemble (members of mixed grid sizes stepped together) through
+the C ABI.
+
+Bars: in eager mode every member's fields are bitwise identical to the same
+case run alone (members of one size class share each launch, but every
+reduction runs over the member's own blocks in the same order); a member agrees
+with the FP64 oracle to the whole-step parity bar; the captured-graph mode
+reproduces eager mode (FP64: identical solves while the iteration caps hold;
+FP32 + learned guess: within the pressure tolerance, each solve at
+||r|| <= p_tol ||b||, the gas and dust mass conserved to round-off); the
+autotuner's cache round-trips.
+"""
+import json
+
+import numpy as np
+import pytest
+
+from paper_1404_0959_amd.inputs import ensemble_cases, make_hit_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1404_0959_amd.pisoc as P
+    P.lib()
+    return P
+
+
+def cases():
+    # interleaved sizes: member -> class mapping is not the identity
+    return [make_hit_case(32, 11, mach=0.2, stokes=(0.1,)),
+            make_hit_case(48, 12, mach=0.5, stokes=(0.3,)),
+            make_hit_case(32, 13, mach=0.5, stokes=(0.05,))]
+
+
+BITS = None
+
+
+def fields(P, get):
+    bits = P.FIELD_RHO | P.FIELD_U | P.FIELD_PHI | P.FIELD_RHO_P | P.FIELD_P
+    return {k: v.cpu().numpy() for k, v in get(bits).items()}
+
+
+def test_eager_members_equal_single_runs(P):
+    cs = cases()
+    kw = dict(p_tol=1e-9, cfl=0.5)
+    ens = P.Ensemble(cs, **kw)
+    singles = [P.Solver.from_case(c, **kw) for c in cs]
+    assert [c["n"] for c in ens.classes()] == [32, 48]
+    assert [c["members"] for c in ens.classes()] == [2, 1]
+    for step in range(3):
+        st, infos = ens.step(1, mode=P.ENS_EAGER)
+        assert st == P.OK
+        for m, s in enumerate(singles):
+            st1, (i1,) = s.step(1)
+            assert st1 == P.OK
+            assert infos[m]["pcg_iters"] == i1["pcg_iters"], (step, m)
+            assert infos[m]["dt"] == i1["dt"] and infos[m]["t"] == i1["t"]
+            assert infos[m]["mass_gas"] == i1["mass_gas"]
+    for m, s in enumerate(singles):
+        a = fields(P, lambda b: ens.fields(m, b))
+        b = fields(P, lambda b: s.fields(b))
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (m, k)
+    st = ens.stats()
+    for m, s in enumerate(singles):
+        assert st[m] == s.stats()
+    t = ens.times()
+    assert t == [s.t for s in singles]
+
+
+def test_member_matches_oracle(P, ora):
+    from test_gpu_parity import compare_state
+    cs = cases()
+    kw = dict(p_tol=1e-8)
+    ens = P.Ensemble(cs, **kw)
+    o = ora.Oracle.from_case(cs[1], **kw)
+    st, infos = ens.step(2, mode=P.ENS_EAGER)
+    st_o, info_o = o.step(2)
+    assert st == st_o == 0
+    assert infos[1]["pcg_iters"] == info_o[-1]["pcg_iters"]
+
+    class View:
+        def fields(self, bits):
+            return ens.fields(1, bits)
+    compare_state(P, ora, View(), o)
+
+
+def test_graph_reproduces_eager_fp64(P):
+    cs = cases()
+    kw = dict(p_tol=1e-9)
+    a = P.Ensemble(cs, **kw)
+    b = P.Ensemble(cs, **kw)
+    for _ in range(4):
+        sa, ia = a.step(1, mode=P.ENS_EAGER)
+    sb, ib = b.step(4, mode=P.ENS_GRAPH)
+    assert sa == sb == P.OK
+    assert b.steps_done == 4
+    for cl in b.classes():
+        assert all(cap > 0 for cap in cl["caps"][:2])
+    for m in range(len(cs)):
+        assert ia[m]["pcg_iters"] == ib[m]["pcg_iters"], m
+        assert ia[m]["t"] == ib[m]["t"]
+        fa = fields(P, lambda bits: a.fields(m, bits))
+        fb = fields(P, lambda bits: b.fields(m, bits))
+        for k in fa:
+            assert np.array_equal(fa[k], fb[k]), (m, k)
+    # further captured steps replay the two parity graphs
+    sb, ib = b.step(3, mode=P.ENS_GRAPH)
+    sa, ia = a.step(3, mode=P.ENS_EAGER)
+    for m in range(len(cs)):
+        assert ia[m]["t"] == ib[m]["t"]
+        fa = fields(P, lambda bits: a.fields(m, bits))
+        fb = fields(P, lambda bits: b.fields(m, bits))
+        assert np.array_equal(fa[P.FIELD_U], fb[P.FIELD_U]), m
+
+
+def test_graph_fp32_learned(P):
+    from paper_1404_0959_amd.learn import load_weights
+    w = load_weights()
+    cs = ensemble_cases(8, seed=3)
+    assert sorted({c.n for c in cs}) == [32, 48, 64]
+    kw = dict(p_tol=1e-6, precision=P.FP32_REFINED, inner_tol=1e-3, guess=P.GUESS_LEARNED,
+              guess_weights=w.data_ptr())
+    a = P.Ensemble(cs, **kw)
+    b = P.Ensemble(cs, **kw)
+    m0 = [s["mass_gas"] for s in b.stats()]
+    p0 = [s["mass_p"][0] for s in b.stats()]
+    sa, ia = a.step(6, mode=P.ENS_EAGER)
+    sb, ib = b.step(6, mode=P.ENS_GRAPH)
+    print("classes", b.classes())
+    for m in range(len(cs)):
+        print(m, cs[m].n, "eager", ia[m]["pcg_iters"], ia[m]["refinements"], "graph",
+              ib[m]["pcg_iters"], ib[m]["refinements"], ib[m]["pcg_relres"], ib[m]["flags"])
+    assert sa in (P.OK, P.WARN_GUESS_FALLBACK) and sb in (P.OK, P.WARN_GUESS_FALLBACK)
+    sb_stats = b.stats()
+    for m in range(len(cs)):
+        assert max(ib[m]["pcg_relres"]) <= 1e-6, ib[m]
+        assert not ib[m]["flags"] & P.FLAG_PCG_MAXIT
+        assert abs(sb_stats[m]["mass_gas"] - m0[m]) <= 1e-10 * m0[m]
+        assert abs(sb_stats[m]["mass_p"][0] - p0[m]) <= 1e-7 * p0[m]
+        ua = a.get(m, P.FIELD_U).cpu().numpy()
+        ub = b.get(m, P.FIELD_U).cpu().numpy()
+        assert np.max(np.abs(ua - ub)) <= 1e-4 * np.max(np.abs(ua)), m
+
+
+def test_autotune_cache_round_trip(P, tmp_path):
+    cs = cases()
+    kw = dict(p_tol=1e-8)
+    path = str(tmp_path / "tune.json")
+    e = P.Ensemble(cs, **kw)
+    with pytest.raises(P.PisocError):
+        e.autotune(path)            # needs one completed step
+    e.step(1, mode=P.ENS_EAGER)
+    e.autotune(path)
+    cache = json.load(open(path))
+    cl = e.classes()
+    assert len(cache) == 2
+    for c in cl:
+        key = [k for k in cache if k.startswith(f"n{c['n']}_b{c['members']}_fp64")]
+        assert len(key) == 1
+        assert cache[key[0]] == [c["block"][0], c["cells_z"]]
+    # tuned shapes still give converged, mass-conserving steps (graph mode)
+    m0 = [s["mass_gas"] for s in e.stats()]
+    st, info = e.step(3, mode=P.ENS_GRAPH)
+    assert st == P.OK
+    for m, i in enumerate(info):
+        assert max(i["pcg_relres"]) <= 1e-8
+        assert abs(i["mass_gas"] - m0[m]) <= 1e-12 * m0[m]
+    # a second ensemble takes the cached shapes without timing
+    e2 = P.Ensemble(cs, **kw)
+    e2.step(1, mode=P.ENS_EAGER)
+    e2.autotune(path)
+    assert [(c["block"], c["cells_z"]) for c in e2.classes()] == \
+        [(c["block"], c["cells_z"]) for c in cl]
+    assert json.load(open(path)) == cache
