@@ -39,14 +39,26 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--mode", default="both", choices=["fp64", "fp32", "both"],
-                    help="both: time plain FP64 and the FP32 mode; the FP32 run is the headline")
-    ap.add_argument("--inner-tol", type=float, default=1e-6)
+    ap.add_argument("--mode", default="all", choices=["fp64", "fp32", "fp32_learned", "all"],
+                    help="all: time plain FP64, FP32 and FP32 + learned guess; the last is the "
+                         "headline")
+    ap.add_argument("--guess-audit", type=int, default=16,
+                    help="learned guess: audit period in steps (0: apply to every solve)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the runs, copy a buffer of this size a few times (a plain copy "
+                         "kernel of known traffic for scaling HBM byte counters)")
+    ap.add_argument("--inner-tol", type=float, default=1e-7)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--p-tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the 64-member mixed-size ensemble measurement")
+    ap.add_argument("--ens-members", type=int, default=64)
+    ap.add_argument("--ens-steps", type=int, default=20)
+    ap.add_argument("--ens-seq-steps", type=int, default=3,
+                    help="timed steps per member of the sequential single-grid runs")
     return ap.parse_args()
 
 
@@ -79,7 +91,8 @@ def timed_run(P, torch, case, prec, args, guess=None):
     """Warm up, then time exactly args.steps steps with per-kernel events on."""
     kw = dict(p_tol=args.p_tol, cfl=0.5, n_corr=2, n_mom_sweeps=4, n_dust_sweeps=4)
     if guess is not None:
-        kw.update(guess=P.GUESS_LEARNED, guess_weights=guess)
+        kw.update(guess=P.GUESS_LEARNED, guess_weights=guess.data_ptr(),
+                  guess_audit=args.guess_audit)
     s = P.Solver.from_case(case, precision=prec, inner_tol=args.inner_tol, **kw)
     st, _ = s.step(args.warmup)
     torch.cuda.synchronize()
@@ -93,6 +106,77 @@ def timed_run(P, torch, case, prec, args, guess=None):
     s.profile(False)
     s.close()
     return t_end - t_start, info, prof
+
+
+def ensemble_run(P, torch, args, weights):
+    """The mixed-size ensemble (32^3, 48^3, 64^3 in the ratio 2:1:1, Mach from
+    {0.2, 0.5}, Stokes U[0.05, 0.5]; FP32 + learned guess) stepped by replaying
+    one captured graph per step after the launch-shape autotuner, against the
+    same members stepped one after another as single grids."""
+    import tempfile
+
+    import numpy as np
+
+    from paper_1404_0959_amd.inputs import ensemble_cases
+    cases = ensemble_cases(args.ens_members, seed=args.seed)
+    cells = sum(c.n ** 3 for c in cases)
+    common = dict(p_tol=args.p_tol, cfl=0.5, n_corr=2, n_mom_sweeps=4, n_dust_sweeps=4)
+    fast = dict(precision=P.FP32_REFINED, inner_tol=args.inner_tol, guess=P.GUESS_LEARNED,
+                guess_weights=weights.data_ptr(), **common)
+    out = {"members": len(cases), "cells": cells,
+           "sizes": {str(n): sum(1 for c in cases if c.n == n) for n in sorted({c.n for c in cases})}}
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(steps)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    E = P.Ensemble(cases, **fast)
+    E.step(1, mode=P.ENS_EAGER)
+    cache = os.path.join(tempfile.gettempdir(), "pisoc_tune.json")
+    t0 = time.perf_counter()
+    E.autotune(cache, force=True)
+    out["autotune_s"] = round(time.perf_counter() - t0, 3)
+    E.step(args.warmup, mode=P.ENS_GRAPH)
+    st_holder = {}
+
+    def graph_steps(k):
+        st_holder["st"], st_holder["info"] = E.step(k, mode=P.ENS_GRAPH)
+    el = timed(graph_steps, args.ens_steps)
+    out["value"] = cells * args.ens_steps / el
+    out["unit"] = "cell-steps/s"
+    out["ms_per_step"] = el * 1e3 / args.ens_steps
+    out["status"] = st_holder["st"]
+    out["max_relres"] = max(max(i["pcg_relres"]) for i in st_holder["info"])
+    out["pcg_iters_mean"] = float(np.mean([np.mean(i["pcg_iters"]) for i in st_holder["info"]]))
+    out["classes"] = [{k: c[k] for k in ("n", "members", "block", "cells_z", "caps", "rounds")}
+                      for c in E.classes()]
+    log(f"ensemble graph: {out['ms_per_step']:.3f} ms/step, {out['value']:.4e} cell-steps/s")
+
+    def eager_steps(k):
+        E.step(k, mode=P.ENS_EAGER)
+    el = timed(eager_steps, max(2, args.ens_steps // 4))
+    out["eager_batched"] = cells * max(2, args.ens_steps // 4) / el
+    E.close()
+    del E
+
+    def sequential(kw, k):
+        total = 0.0
+        for c in cases:
+            s = P.Solver.from_case(c, **kw)
+            s.step(1)
+            torch.cuda.synchronize()
+            total += timed(lambda j: s.step(j), k) / k
+            s.close()
+        return cells / total
+    out["sequential_plain_fp64"] = sequential(dict(precision=P.FP64, **common), args.ens_seq_steps)
+    out["sequential_fp32_learned"] = sequential(fast, args.ens_seq_steps)
+    out["vs_sequential_plain"] = out["value"] / out["sequential_plain_fp64"]
+    out["vs_sequential_same_method"] = out["value"] / out["sequential_fp32_learned"]
+    log(f"ensemble: {json.dumps(out)}")
+    return out
 
 
 def roofline(prof):
@@ -132,20 +216,37 @@ def main():
     log(f"inputs {case.name} ready in {time.time() - t0:.1f}s")
     n3 = args.n ** 3
 
+    if args.calib_copy_mib > 0:
+        a = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.calib_copy_mib} MiB")
+        del a, b
+
+    from paper_1404_0959_amd.learn import load_weights
+    weights = load_weights()
     runs = {}
-    modes = ["fp64", "fp32"] if args.mode == "both" else [args.mode]
+    modes = ["fp64", "fp32", "fp32_learned"] if args.mode == "all" else [args.mode]
     for m in modes:
         prec = P.FP64 if m == "fp64" else P.FP32_REFINED
-        el, info, prof = timed_run(P, torch, case, prec, args)
+        el, info, prof = timed_run(P, torch, case, prec, args,
+                                   guess=weights if m == "fp32_learned" else None)
         iters = [i["pcg_iters"] for i in info]
         runs[m] = dict(elapsed=el, info=info, prof=prof, value=n3 * args.steps / el,
-                       iters=float(np.mean([sum(i) / len(i) for i in iters])))
+                       iters=float(np.mean([sum(i) / len(i) for i in iters])),
+                       guess_steps=sum(1 for i in info if not i["flags"] & P.FLAG_GUESS_SKIPPED))
         log(f"{m}: {el * 1e3 / args.steps:.3f} ms/step, {n3 * args.steps / el:.4e} cell-steps/s, "
             f"mean CG iterations per solve {runs[m]['iters']:.2f}")
-    head = "fp32" if "fp32" in runs else modes[0]
+    head = modes[-1]
     H = runs[head]
     roof, kernels = roofline(H["prof"])
     log(json.dumps(kernels))
+
+    ens = None
+    if not args.no_ensemble:
+        ens = ensemble_run(P, torch, args, weights)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -164,21 +265,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head == "fp64" else "f32",
+        "dtype": "f64" if head == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"decaying HIT {args.n}^3, Mach 0.2, 1 dust class St 0.2, "
                                f"CFL 0.5, 2 PISO correctors, Jacobi-PCG rel. residual "
                                f"{args.p_tol:g}, seed {args.seed}",
-                   "grid": args.n, "mode": head, "guess": "zero"},
+                   "grid": args.n, "mode": head,
+                   "guess": (f"learned, audited every {args.guess_audit} steps"
+                             if head == "fp32_learned" else "zero")},
         "roofline": roof,
         "cpu_baseline": cpu,
         "pcg_iters_mean": H["iters"],
         "modes": {m: {"value": r["value"], "ms_per_step": r["elapsed"] * 1e3 / args.steps,
-                      "pcg_iters_mean": r["iters"]} for m, r in runs.items()},
+                      "pcg_iters_mean": r["iters"], "steps_with_guess": r["guess_steps"]
+                      if m == "fp32_learned" else 0} for m, r in runs.items()},
         "kernels": kernels,
+        "ensemble": ens,
     }
-    if "fp64" in runs and "fp32" in runs:
-        out["speedup_vs_fp64"] = runs["fp32"]["value"] / runs["fp64"]["value"]
+    if "fp64" in runs and head != "fp64":
+        out["speedup_vs_fp64"] = runs[head]["value"] / runs["fp64"]["value"]
     print(json.dumps(out), flush=True)
 
 

@@ -73,7 +73,8 @@ enum {
     PISOC_FLAG_NONFINITE = 2,
     PISOC_FLAG_RHO_NONPOS = 4,
     PISOC_FLAG_GUESS_FALLBACK = 8,
-    PISOC_FLAG_BAD_DT = 16
+    PISOC_FLAG_BAD_DT = 16,
+    PISOC_FLAG_GUESS_SKIPPED = 32
 };
 
 typedef struct {
@@ -98,6 +99,13 @@ typedef struct {
     int32_t max_refine;        /* FP32_REFINED: cap on FP64 refinement rounds per solve */
     int32_t capture;           /* != 0: keep corrector-1 pressure system of the last step
                                   (b, p', p0, diag) for pisoc_fields */
+    int32_t guess_audit;       /* learned guess, pisoc_step: 0 = apply it to every solve;
+                                  k > 0 = apply it to a corrector's solve only while the CG
+                                  iterations it saves (running means of solves with and
+                                  without it) exceed its own cost in CG-iteration
+                                  equivalents (timed with events), trying the other choice
+                                  once every k steps (PISOC_FLAG_GUESS_SKIPPED marks steps
+                                  that went without it) */
 } pisoc_params;
 
 typedef struct {

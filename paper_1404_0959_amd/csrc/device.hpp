@@ -73,25 +73,32 @@ struct DevState {
     int32_t it_later_max[kMaxCorr];
 };
 
-// Geometry of a launch: blocks of 64x4 (or 32x8) threads over x-y, each
-// thread walking `cz` consecutive cells along z.
+// A cell and the periodic offsets to the cells up to two steps away along
+// each axis (every stencil here reaches at most two cells): computed once per
+// cell, so that each neighbour address is one add.
 struct CellIdx {
-    int n, i, j, k;
-    size_t base;   // first cell of the member
-    __device__ inline size_t at(int di, int dj, int dk) const {
-        int a = i + di, b = j + dj, c = k + dk;
+    size_t p;               // this cell (member base included)
+    int off[3][5];          // off[d][s + 2]: index offset of the cell s steps along d
+    __device__ inline CellIdx(int n, int i, int j, int k, size_t base) {
+        p = base + (size_t)i + (size_t)n * ((size_t)j + (size_t)n * (size_t)k);
+        const int nn = n * n;
+#pragma unroll
+        for (int s = -2; s <= 2; ++s) {
+            off[0][s + 2] = wrap_delta(i, s, n);
+            off[1][s + 2] = wrap_delta(j, s, n) * n;
+            off[2][s + 2] = wrap_delta(k, s, n) * nn;
+        }
+    }
+    static __device__ inline int wrap_delta(int i, int s, int n) {
+        int a = i + s;
         a = a < 0 ? a + n : (a >= n ? a - n : a);
-        b = b < 0 ? b + n : (b >= n ? b - n : b);
-        c = c < 0 ? c + n : (c >= n ? c - n : c);
-        return base + (size_t)a + (size_t)n * ((size_t)b + (size_t)n * (size_t)c);
+        return a - i;
     }
-    // cell reached by s steps along axis d
+    // cell reached by s steps along axis d (|s| <= 2)
     __device__ inline size_t sh(int d, int s) const {
-        return d == 0 ? at(s, 0, 0) : (d == 1 ? at(0, s, 0) : at(0, 0, s));
+        return p + (size_t)(ptrdiff_t)off[d][s + 2];
     }
-    __device__ inline size_t self() const {
-        return base + (size_t)i + (size_t)n * ((size_t)j + (size_t)n * (size_t)k);
-    }
+    __device__ inline size_t self() const { return p; }
 };
 
 // Fourth-order central interpolation onto face P + (s + 1/2) e_d:
@@ -109,6 +116,34 @@ __device__ inline R i4r(const T* __restrict__ q, const CellIdx& c, int d, int s)
     R a = (R)q[c.sh(d, s - 1)], b = (R)q[c.sh(d, s)], e = (R)q[c.sh(d, s + 1)],
       f = (R)q[c.sh(d, s + 2)];
     return (R(9) * (b + e) - (a + f)) * R(0.0625);
+}
+
+// A field on the cross-shaped stencil of reach 2, gathered into registers so
+// that all of its loads are in flight together: v[0] is the cell, v[1 + 4d + t]
+// the cells -2, -1, +1, +2 (t = 0..3) steps along axis d.
+template <typename T>
+__device__ inline void gather13(const T* __restrict__ q, const CellIdx& c, T (&v)[13]) {
+    v[0] = q[c.self()];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        v[1 + 4 * d] = q[c.sh(d, -2)];
+        v[2 + 4 * d] = q[c.sh(d, -1)];
+        v[3 + 4 * d] = q[c.sh(d, 1)];
+        v[4 + 4 * d] = q[c.sh(d, 2)];
+    }
+}
+
+// The gathered value s steps along d (|s| <= 2).
+template <typename T>
+__device__ inline T g13(const T (&v)[13], int d, int s) {
+    return s == 0 ? v[0] : v[1 + 4 * d + (s < 0 ? s + 2 : s + 1)];
+}
+
+// I4 onto face P + (s + 1/2) e_d from gathered values (same operations as i4).
+template <typename T>
+__device__ inline T i4g(const T (&v)[13], int d, int s) {
+    const T a = g13(v, d, s - 1), b = g13(v, d, s), e = g13(v, d, s + 1), f = g13(v, d, s + 2);
+    return (T(9) * (b + e) - (a + f)) * T(0.0625);
 }
 
 // Gauss-theorem cell derivative along d from I4 face values.

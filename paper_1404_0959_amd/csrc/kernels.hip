@@ -28,7 +28,7 @@ namespace pisoc {
     for (int zz_ = 0; zz_ < (ph).cz; ++zz_) {                                \
         const int ck_ = bz_ * (ph).cz + zz_;                                 \
         if (ci_ >= (ph).n || cj_ >= (ph).n || ck_ >= (ph).n) continue;       \
-        const CellIdx c{(ph).n, ci_, cj_, ck_, base_};                       \
+        const CellIdx c((ph).n, ci_, cj_, ck_, base_);                       \
         const size_t P = c.self();
 #define END_CELLS }
 
@@ -177,32 +177,39 @@ __global__ void __launch_bounds__(kBlock) k_mom_sweep(Phys ph, const DevState* s
     const T inv_V = (T)ph.inv_V, inv_h = (T)ph.inv_h;
     const T mu_h2 = (T)(ph.mu * ph.inv_h2);
     FOR_CELLS(ph)
-    T fp[3], fm[3];
-    T dphi = T(0);
+    // every load of the cell first (the 13-point stencils of the three
+    // components and of p^n, the six fluxes), then the arithmetic
+    T u[3][13], pv[13], fp[3], fm[3], sv[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) gather13(uin + m * N, c, u[m]);
+    if (!HBYA) gather13(pn, c, pv);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         fp[d] = phi[d * N + P];
         fm[d] = phi[d * N + c.sh(d, -1)];
-        dphi += fp[d] - fm[d];
+        sv[d] = s[d * N + P];
     }
-    dphi *= inv_V;
     const T a = aP[P];
+    T dphi = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dphi += fp[d] - fm[d];
+    dphi *= inv_V;
+    const T ia = T(1) / a;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        const T* q = uin + m * N;
         T conv = T(0), nb = T(0);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            conv += fp[d] * i4(q, c, d, 0) - fm[d] * i4(q, c, d, -1);
-            nb += q[c.sh(d, 1)] + q[c.sh(d, -1)];
+            conv += fp[d] * i4g(u[m], d, 0) - fm[d] * i4g(u[m], d, -1);
+            nb += g13(u[m], d, 1) + g13(u[m], d, -1);
         }
-        T off = conv * inv_V - T(0.5625) * dphi * q[P] - mu_h2 * nb;
-        T rhs = s[m * N + P] - off;
-        if (!HBYA) rhs -= dgauss(pn, c, m, inv_h);
-        uout[m * N + P] = rhs / a;
+        T off = conv * inv_V - T(0.5625) * dphi * u[m][0] - mu_h2 * nb;
+        T rhs = sv[m] - off;
+        if (!HBYA) rhs -= (i4g(pv, m, 0) - i4g(pv, m, -1)) * inv_h;
+        uout[m * N + P] = rhs * ia;
     }
     if (HBYA) {
-        w[P] = ((T)(st + mem_)->rho_ref + rk[P]) / a;
+        w[P] = ((T)(st + mem_)->rho_ref + rk[P]) * ia;
         p0[P] = pdev(rk[P], (st + mem_)->rho_ref, (st + mem_)->p_ref, ph.gamma);
     }
     END_CELLS

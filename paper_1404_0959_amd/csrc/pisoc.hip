@@ -144,6 +144,7 @@ bool valid_params(const pisoc_params* p, std::string* why) {
     if (p->guess != PISOC_GUESS_ZERO && p->guess != PISOC_GUESS_LEARNED) return fail("unknown guess");
     if (p->guess == PISOC_GUESS_LEARNED && (!p->d_guess_weights || p->n % 16 != 0))
         return fail("learned guess needs d_guess_weights and n % 16 == 0");
+    if (p->guess_audit < 0) return fail("guess_audit must be >= 0");
     return true;
 }
 
@@ -212,6 +213,18 @@ struct pisoc_ctx {
     int cap_later;
     int rounds;
     size_t es;      // bytes per field element (8 or 4)
+    // learned-guess audit of eager steps (guess_audit > 0): running means of the
+    // CG iterations of each corrector's solve with and without the guess, and
+    // of the guess's cost in CG-iteration equivalents (timed with events);
+    // < 0: not measured yet
+    struct Audit {
+        double it_zero[PISOC_MAX_CORR], it_guess[PISOC_MAX_CORR];
+        double cost;
+        bool use[PISOC_MAX_CORR];   // this step's choice
+        int64_t steps;
+        hipEvent_t ev[PISOC_MAX_CORR][3];
+        bool have_events;
+    } audit;
     Prof prof;
     std::string err;
     std::vector<double> rho_ref, p_ref;  // per member
@@ -462,7 +475,7 @@ template <typename T>
 T* ucur_of(const pisoc_ctx* ctx, StepPtrs<T>& S) { return ctx->ucur_slot == 1 ? S.ua : S.ub; }
 
 template <typename T>
-void enqueue_corr_setup(pisoc_ctx* ctx, StepPtrs<T>& S, int corr) {
+void enqueue_corr_setup(pisoc_ctx* ctx, StepPtrs<T>& S, int corr, bool guess) {
     using O = Ops<T>;
     const Phys& ph = ctx->ph;
     const Launch& L = ctx->L;
@@ -478,8 +491,7 @@ void enqueue_corr_setup(pisoc_ctx* ctx, StepPtrs<T>& S, int corr) {
                     ctx->part(PS_U), cap ? S.snap : nullptr, cap ? S.snap + N : nullptr,
                     cap ? S.snap + 2 * N : nullptr, S.b64, S.x64a);
     });
-    if (ctx->prm.guess == PISOC_GUESS_LEARNED)
-        learned_guess<T>(ctx, S.r, S.x, S.dg, S.w, S.p0, S.pp0, S.q);
+    if (guess) learned_guess<T>(ctx, S.r, S.x, S.dg, S.w, S.p0, S.pp0, S.q);
 }
 
 template <typename T>
@@ -594,6 +606,49 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool eager, pisoc_
     Ops<float>::cast_in(s, xa, S.x, ctx->NT(), 0.0);
 }
 
+bool audit_on(const pisoc_ctx* ctx) {
+    return ctx->prm.guess == PISOC_GUESS_LEARNED && ctx->prm.guess_audit > 0 && ctx->audit.have_events;
+}
+
+// The guess is used for a solve when the iterations it saves exceed its cost
+// (both as running means); until both options have been measured each is
+// tried once, and every guess_audit-th step takes the other option once so
+// that the mean of the unused one stays current.
+void audit_decide(pisoc_ctx* ctx) {
+    auto& A = ctx->audit;
+    const bool probe = A.steps % ctx->prm.guess_audit == ctx->prm.guess_audit - 1;
+    for (int c = 0; c < ctx->prm.n_corr; ++c) {
+        bool use;
+        if (A.it_guess[c] < 0.0) use = true;
+        else if (A.it_zero[c] < 0.0) use = false;
+        else {
+            const bool pays = A.it_zero[c] - A.it_guess[c] > std::max(A.cost, 0.0);
+            use = probe ? !pays : pays;
+        }
+        A.use[c] = use;
+    }
+}
+
+// After the step's last synchronisation: fold its iterations and timings in.
+void audit_update(pisoc_ctx* ctx) {
+    auto& A = ctx->audit;
+    auto mean = [](double old, double x) { return old < 0.0 ? x : 0.5 * (old + x); };
+    for (int c = 0; c < ctx->prm.n_corr; ++c) {
+        int it = 0;
+        for (int m = 0; m < ctx->batch; ++m) it = std::max(it, ctx->hst[m].it_corr[c]);
+        if (!A.use[c]) {
+            A.it_zero[c] = mean(A.it_zero[c], it);
+            continue;
+        }
+        A.it_guess[c] = mean(A.it_guess[c], it);
+        float t_guess = 0.f, t_solve = 0.f;
+        if (hipEventElapsedTime(&t_guess, A.ev[c][0], A.ev[c][1]) == hipSuccess &&
+            hipEventElapsedTime(&t_solve, A.ev[c][1], A.ev[c][2]) == hipSuccess && t_solve > 0.f)
+            A.cost = mean(A.cost, (double)t_guess / ((double)t_solve / std::max(it, 1)));
+    }
+    A.steps += 1;
+}
+
 // Launch sequence of one step of every member.  eager: with host waits in the
 // pressure solves; otherwise the fixed sequence for graph capture.
 template <typename T>
@@ -602,8 +657,12 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
     StepPtrs<T> S = step_ptrs<T>(ctx);
     hipStream_t s = ctx->stream;
     enqueue_front<T>(ctx, S);
+    const bool audit = eager && audit_on(ctx);
     for (int corr = 0; corr < p.n_corr; ++corr) {
-        enqueue_corr_setup<T>(ctx, S, corr);
+        const bool guess = p.guess == PISOC_GUESS_LEARNED && (!audit || ctx->audit.use[corr]);
+        if (audit && guess) (void)hipEventRecord(ctx->audit.ev[corr][0], s);
+        enqueue_corr_setup<T>(ctx, S, corr, guess);
+        if (audit && guess) (void)hipEventRecord(ctx->audit.ev[corr][1], s);
         pisoc_status err = PISOC_OK;
         if constexpr (sizeof(T) == sizeof(float)) {
             solve_fp32(ctx, S, corr, eager, &err);
@@ -617,6 +676,7 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
             record_solve(s, ctx->st, ctx->batch, corr, /*round=*/0, /*add=*/1, /*fin=*/1);
         }
         if (err != PISOC_OK) return err;
+        if (audit && guess) (void)hipEventRecord(ctx->audit.ev[corr][2], s);
         if (eager) {
             for (int m = 0; m < ctx->batch; ++m)
                 if (ctx->hst[m].flags & PISOC_FLAG_BAD_DT) {
@@ -680,11 +740,17 @@ pisoc_status combine_status(pisoc_status a, pisoc_status b) {
 // records.  The step is checked before it is committed: if any member
 // diverged, no member advances.
 pisoc_status eager_step(pisoc_ctx* ctx, pisoc_step_info* info) {
+    if (audit_on(ctx)) audit_decide(ctx);
     pisoc_status st = ctx->prm.precision == PISOC_FP64 ? enqueue_step<double>(ctx, true)
                                                        : enqueue_step<float>(ctx, true);
     if (st != PISOC_OK) return st;
     if ((st = sync_state(ctx)) != PISOC_OK) return st;
     if (ctx->prof.on) ctx->prof.resolve(kIterInf);
+    int skipped = 0;
+    if (audit_on(ctx)) {
+        audit_update(ctx);
+        for (int c = 0; c < ctx->prm.n_corr; ++c) skipped |= ctx->audit.use[c] ? 0 : PISOC_FLAG_GUESS_SKIPPED;
+    }
     pisoc_status worst = PISOC_OK;
     bool bad = false;
     for (int m = 0; m < ctx->batch; ++m) {
@@ -707,7 +773,10 @@ pisoc_status eager_step(pisoc_ctx* ctx, pisoc_step_info* info) {
         return PISOC_ERR_DIVERGED;
     }
     if (info)
-        for (int m = 0; m < ctx->batch; ++m) fill_info(ctx, ctx->hst[m], false, info + m);
+        for (int m = 0; m < ctx->batch; ++m) {
+            fill_info(ctx, ctx->hst[m], false, info + m);
+            info[m].flags |= skipped;
+        }
     rotate(ctx);
     commit(ctx->stream, ctx->st, ctx->batch);
     ctx->t += ctx->hst[0].dt;
@@ -753,6 +822,24 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     ctx->pred_later = 0;
     ctx->cap_later = 0;
     ctx->rounds = 0;
+    for (int c = 0; c < PISOC_MAX_CORR; ++c) {
+        ctx->audit.it_zero[c] = -1.0;
+        ctx->audit.it_guess[c] = -1.0;
+        ctx->audit.use[c] = true;
+    }
+    ctx->audit.cost = -1.0;
+    ctx->audit.steps = 0;
+    ctx->audit.have_events = false;
+    if (prm->guess == PISOC_GUESS_LEARNED && prm->guess_audit > 0) {
+        bool ok = true;
+        for (auto& row : ctx->audit.ev)
+            for (auto& e : row) ok = ok && hipEventCreate(&e) == hipSuccess;
+        ctx->audit.have_events = ok;
+        if (!ok) {
+            ctx->err = "hipEventCreate failed";
+            return PISOC_ERR_HIP;
+        }
+    }
     ctx->es = prm->precision == PISOC_FP64 ? sizeof(double) : sizeof(float);
     ctx->prof.reset();
     if (hipHostMalloc(reinterpret_cast<void**>(&ctx->hst), sizeof(DevState) * (size_t)batch,
@@ -822,6 +909,9 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
 
 void free_ctx(pisoc_ctx* ctx) {
     if (!ctx) return;
+    if (ctx->audit.have_events)
+        for (auto& row : ctx->audit.ev)
+            for (auto& e : row) (void)hipEventDestroy(e);
     if (ctx->hst) (void)hipHostFree(ctx->hst);
     delete ctx;
 }
@@ -1181,7 +1271,8 @@ bool same_class_params(const pisoc_params& a, const pisoc_params& b) {
            a.n_dust_sweeps == b.n_dust_sweeps && a.p_tol == b.p_tol && a.p_maxit == b.p_maxit &&
            a.precision == b.precision && a.guess == b.guess &&
            a.d_guess_weights == b.d_guess_weights && a.inner_tol == b.inner_tol &&
-           a.max_refine == b.max_refine && a.capture == b.capture;
+           a.max_refine == b.max_refine && a.capture == b.capture &&
+           a.guess_audit == b.guess_audit;
 }
 
 // Size classes in order of first appearance; returns false on invalid input.

@@ -21,6 +21,7 @@ ERR_INVALID, ERR_HIP, ERR_DIVERGED, ERR_WORKSPACE = -1, -2, -3, -4
 FP64, FP32_REFINED = 0, 1
 GUESS_ZERO, GUESS_LEARNED = 0, 1
 FLAG_PCG_MAXIT, FLAG_NONFINITE, FLAG_RHO_NONPOS, FLAG_GUESS_FALLBACK, FLAG_BAD_DT = 1, 2, 4, 8, 16
+FLAG_GUESS_SKIPPED = 32
 
 FIELD_RHO, FIELD_U, FIELD_PHI, FIELD_RHO_P, FIELD_P = 1, 2, 4, 8, 16
 FIELD_PSOLVE_B, FIELD_PSOLVE_X, FIELD_P_PREV, FIELD_PSOLVE_DIAG = 32, 64, 128, 256
@@ -55,7 +56,7 @@ class Params(C.Structure):
         ("precision", C.c_int32), ("guess", C.c_int32),
         ("d_guess_weights", C.c_void_p),
         ("inner_tol", C.c_double), ("max_refine", C.c_int32),
-        ("capture", C.c_int32),
+        ("capture", C.c_int32), ("guess_audit", C.c_int32),
     ]
 
 
@@ -193,8 +194,8 @@ def _stream_ptr(torch, stream):
 
 def make_params(n, *, gamma, C_, mu, tau_p=(), cfl=0.5, dt_growth=1.2, dt_fixed=0.0, dt_max=0.0,
                 n_corr=2, n_mom_sweeps=4, n_dust_sweeps=4, p_tol=1e-8, p_maxit=500,
-                precision=FP64, guess=GUESS_ZERO, guess_weights=None, inner_tol=1e-3,
-                max_refine=20, capture=False) -> Params:
+                precision=FP64, guess=GUESS_ZERO, guess_weights=None, inner_tol=1e-7,
+                max_refine=20, capture=False, guess_audit=0) -> Params:
     p = Params()
     p.n = n
     p.n_classes = len(tau_p)
@@ -208,6 +209,7 @@ def make_params(n, *, gamma, C_, mu, tau_p=(), cfl=0.5, dt_growth=1.2, dt_fixed=
     p.d_guess_weights = guess_weights
     p.inner_tol, p.max_refine = inner_tol, max_refine
     p.capture = 1 if capture else 0
+    p.guess_audit = guess_audit
     return p
 
 

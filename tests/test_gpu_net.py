@@ -148,3 +148,28 @@ def test_step_with_learned_guess(P, ora, small_dataset):
         print("iterations zero", [i["pcg_iters"] for i in ia], "learned",
               [i["pcg_iters"] for i in ib], "fallbacks",
               sum(1 for i in ib if i["flags"] & P.FLAG_GUESS_FALLBACK))
+
+
+def test_guess_audit(P):
+    """With guess_audit the guess is tried on the first step and the zero guess
+    on the second; afterwards each solve takes whichever pays (the trained
+    weights, 32^3), every solve still meets the tolerance and the state stays
+    within the solver tolerance of the plain run."""
+    from paper_1404_0959_amd.inputs import make_hit_case
+    from paper_1404_0959_amd.learn import load_weights
+    w = load_weights()
+    case = make_hit_case(32, 21, mach=0.2, stokes=(0.1,))
+    a = P.Solver.from_case(case, p_tol=1e-8)
+    b = P.Solver.from_case(case, p_tol=1e-8, guess=P.GUESS_LEARNED, guess_weights=w.data_ptr(),
+                           guess_audit=4)
+    sa, ia = a.step(12)
+    sb, ib = b.step(12)
+    assert sa == 0 and sb in (0, P.WARN_GUESS_FALLBACK)
+    skipped = [bool(i["flags"] & P.FLAG_GUESS_SKIPPED) for i in ib]
+    assert not skipped[0] and skipped[1], skipped
+    for i in ib:
+        assert max(i["pcg_relres"]) <= 1e-8
+    ua = a.get(P.FIELD_U).cpu().numpy()
+    ub = b.get(P.FIELD_U).cpu().numpy()
+    assert np.max(np.abs(ua - ub)) <= 1e-4 * np.max(np.abs(ua))
+    print("audit: skipped", skipped, "iterations", [i["pcg_iters"] for i in ib])
