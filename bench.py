@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the runs, copy a buffer of this size a few times (a plain copy "
                          "kernel of known traffic for scaling HBM byte counters)")
-    ap.add_argument("--inner-tol", type=float, default=1e-7)
+    ap.add_argument("--inner-tol", type=float, default=1e-6)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--p-tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -153,10 +153,40 @@ __device__ inline T dgauss(const T* __restrict__ q, const CellIdx& c, int d, T i
 }
 
 __device__ inline int flat_tid() { return threadIdx.x + blockDim.x * threadIdx.y; }
-__device__ inline unsigned flat_bid() {
-    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-}
 __device__ inline unsigned num_blocks() { return gridDim.x * gridDim.y * gridDim.z; }
+
+constexpr unsigned kXcds = 8;   // accelerator complex dies, each with its own L2
+
+// Logical number of this block.  The blocks of a launch are dealt to the XCDs
+// round-robin in order of their hardware number; renumbering them so that each
+// XCD receives one contiguous range of logical numbers keeps neighbouring tiles,
+// and the halo cells they share, in the same XCD's L2.  Tiles, members and
+// reduction partials are all indexed by the logical number.
+__device__ inline unsigned flat_bid() {
+    const unsigned f = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned B = num_blocks();
+    return B % kXcds == 0 ? (f % kXcds) * (B / kXcds) + f / kXcds : f;
+}
+
+// Logical 3D block coordinates (x fastest) of this block.
+struct BlockXYZ {
+    int x, y, z;
+};
+__device__ inline BlockXYZ block_xyz() {
+    const unsigned L = flat_bid();
+    return {(int)(L % gridDim.x), (int)((L / gridDim.x) % gridDim.y),
+            (int)(L / (gridDim.x * gridDim.y))};
+}
+
+// Barrier that orders only LDS accesses across the block: it waits for this
+// wave's LDS operations, not for its global loads in flight, so loads issued
+// for a later plane of a z-march stay in flight across it (a plain
+// __syncthreads() also waits for every outstanding global access).
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 template <bool MAX>
 __device__ inline double combine(double a, double b) {

@@ -15,16 +15,17 @@ namespace pisoc {
 // The member of this block (blocks of member m have blockIdx.z in
 // [m nz, (m+1) nz)), its z-block and its first cell.
 #define MEMBER(ph)                                                           \
-    const int mem_ = (int)(blockIdx.z / (unsigned)(ph).nz);                  \
-    const int bz_ = (int)blockIdx.z - mem_ * (ph).nz;                        \
+    const BlockXYZ bp_ = block_xyz();                                        \
+    const int mem_ = bp_.z / (ph).nz;                                        \
+    const int bz_ = bp_.z - mem_ * (ph).nz;                                  \
     const size_t base_ = (size_t)mem_ * (ph).N;                              \
     (void)bz_;                                                               \
     (void)base_;
 // true in one thread of the member's first block
-#define MEMBER_FIRST() (blockIdx.x == 0 && blockIdx.y == 0 && bz_ == 0 && flat_tid() == 0)
+#define MEMBER_FIRST() (bp_.x == 0 && bp_.y == 0 && bz_ == 0 && flat_tid() == 0)
 #define FOR_CELLS(ph)                                                        \
-    const int ci_ = blockIdx.x * blockDim.x + threadIdx.x;                   \
-    const int cj_ = blockIdx.y * blockDim.y + threadIdx.y;                   \
+    const int ci_ = bp_.x * blockDim.x + threadIdx.x;                        \
+    const int cj_ = bp_.y * blockDim.y + threadIdx.y;                        \
     for (int zz_ = 0; zz_ < (ph).cz; ++zz_) {                                \
         const int ck_ = bz_ * (ph).cz + zz_;                                 \
         if (ci_ >= (ph).n || cj_ >= (ph).n || ck_ >= (ph).n) continue;       \
@@ -439,7 +440,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     const T inv_h2 = (T)ph.inv_h2;
     const int n = ph.n, cz = ph.cz;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kTX * ty;
-    const int i0 = blockIdx.x * kTX, j0 = blockIdx.y * kTY;
+    const int i0 = bp_.x * kTX, j0 = bp_.y * kTY;
     const int k0 = bz_ * cz;
     const int k1 = k0 + cz < n ? k0 + cz : n;
     const size_t nn = (size_t)n * n;
@@ -483,18 +484,41 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
         hoff = base_ + (size_t)wr(i0 - 1 + hx) + (size_t)n * (j0 + y);
         hkind = 2;
     }
+    // Software pipeline: the loads of plane kk + 1 (w at kk + 3; r, diag, p_old
+    // at kk + 2; this thread's halo cell of plane kk + 1) are issued before the
+    // LDS stores and barrier of plane kk, so their latency overlaps its work.
+    // Every load is unconditional and in bounds (threads without a halo cell
+    // read their own), so no branch forces the loads to drain early.
+    const T* hsrc = hkind == 1 ? w : r;                 // w halo, or r of the p halo
+    const size_t hq = hkind == 0 ? col : hoff;          // plane offset added per plane
+    auto sel = [&](T v) { return first ? T(0) : v; };
+    T wq4 = w[col + nn * wr(k0 + 2)];
+    T rn1 = r[col + nn * wr(k0 + 1)], dn1 = diag[col + nn * wr(k0 + 1)];
+    T on1 = pold[col + nn * wr(k0 + 1)];   // raw; the select is applied at its use
+    T ha = hsrc[nn * (size_t)k0 + hq], hd = diag[nn * (size_t)k0 + hq];
+    T ho = pold[nn * (size_t)k0 + hq];
     double acc = 0.0;
     for (int kk = k0; kk < k1; ++kk) {
         const size_t pl = nn * (size_t)kk;
-        const T wq4 = w[col + nn * wr(kk + 2)];
-        const size_t Qn = col + nn * wr(kk + 1);
-        const T dn = diag[Qn];
-        const T pp = first ? r[Qn] / dn : r[Qn] / dn + beta * pold[Qn];
+        const T wq4c = wq4, dn = dn1;
+        const T pp = rn1 / dn1 + beta * sel(on1);
+        const T hwc = ha, hpc = ha / hd + beta * sel(ho);
+        {
+            const size_t Qf = col + nn * wr(kk + 2);
+            const size_t Hf = nn * (size_t)wr(kk + 1) + hq;
+            wq4 = w[col + nn * wr(kk + 3)];
+            rn1 = r[Qf];
+            dn1 = diag[Qf];
+            on1 = pold[Qf];
+            ha = hsrc[Hf];
+            hd = diag[Hf];
+            ho = pold[Hf];
+        }
         ws[ty + 2][tx + 2] = wq2;
         ps[ty + 1][tx + 1] = pc;
-        if (hkind == 1) ws[hy][hx] = w[pl + hoff];
-        else if (hkind == 2) ps[hy][hx] = dirv(pl + hoff);
-        __syncthreads();
+        if (hkind == 1) ws[hy][hx] = hwc;
+        else if (hkind == 2) ps[hy][hx] = hpc;
+        lds_barrier();
         const T kxp = (T(9) * (ws[ty + 2][tx + 2] + ws[ty + 2][tx + 3]) -
                        (ws[ty + 2][tx + 1] + ws[ty + 2][tx + 4])) * T(0.0625);
         const T kxm = (T(9) * (ws[ty + 2][tx + 1] + ws[ty + 2][tx + 2]) -
@@ -503,7 +527,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
                        (ws[ty + 1][tx + 2] + ws[ty + 4][tx + 2])) * T(0.0625);
         const T kym = (T(9) * (ws[ty + 1][tx + 2] + ws[ty + 2][tx + 2]) -
                        (ws[ty][tx + 2] + ws[ty + 3][tx + 2])) * T(0.0625);
-        const T kzp = (T(9) * (wq2 + wq3) - (wq1 + wq4)) * T(0.0625);
+        const T kzp = (T(9) * (wq2 + wq3) - (wq1 + wq4c)) * T(0.0625);
         const T kzm = (T(9) * (wq1 + wq2) - (wq0 + wq3)) * T(0.0625);
         const T lap = kxp * (pc - ps[ty + 1][tx + 2]) + kxm * (pc - ps[ty + 1][tx]) +
                       kyp * (pc - ps[ty + 2][tx + 1]) + kym * (pc - ps[ty][tx + 1]) +
@@ -513,11 +537,11 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
         q[col + pl] = qv;
         pnew[col + pl] = pc;
         acc += (double)pc * (double)qv;
-        __syncthreads();
+        lds_barrier();
         wq0 = wq1;
         wq1 = wq2;
         wq2 = wq3;
-        wq3 = wq4;
+        wq3 = wq4c;
         pm = pc;
         pc = pp;
         dc = dn;

@@ -111,6 +111,92 @@ __global__ void __launch_bounds__(256) k_conv(int n, int batch, const uint16_t* 
     }
 }
 
+// Forward pass of a 16-input-channel layer with input reuse across output
+// rows.  A wavefront owns 16 cells along x of a block of kRY x kRZ output rows
+// (y, z).  It walks the (kRY + 2) x (kRZ + 2) input rows that block touches;
+// each input row, taken at the three x shifts, is loaded once (8 bytes per
+// lane: 4 channels of one cell) and fed to the matrix cores for every output
+// row and tap it contributes to -- 432 products per 108 loads, where the
+// row-at-a-time kernel issues one load per product.  Output as k_conv
+// (ReLU to BF16, or with FINAL channel 0 in FP32 times yscale).
+constexpr int kRY = 4, kRZ = 4;
+
+template <bool FINAL>
+__global__ void __launch_bounds__(256) k_conv16_rows(int n, int batch,
+                                                     const uint16_t* __restrict__ in,
+                                                     const v4s* __restrict__ wpk, int relu,
+                                                     uint16_t* __restrict__ out,
+                                                     float* __restrict__ yout, float yscale) {
+    const int lane = threadIdx.x & 63;
+    const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int segs = n / 16, nyb = n / kRY, nzb = n / kRZ;
+    const long nwaves = (long)batch * nzb * nyb * segs;
+    if (wave >= nwaves) return;  // whole wavefront; no block barrier below
+    const int iseg = (int)(wave % segs);
+    long rest = wave / segs;
+    const int j0 = (int)(rest % nyb) * kRY;
+    rest /= nyb;
+    const int k0 = (int)(rest % nzb) * kRZ;
+    const int b = (int)(rest / nzb);
+    const size_t N = (size_t)n * n * n;
+    const int m = lane & 15, g = lane >> 4;
+    v4s B[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) B[t] = wpk[t * 64 + lane];
+    v4f acc[kRY][kRZ];
+#pragma unroll
+    for (int oy = 0; oy < kRY; ++oy)
+#pragma unroll
+        for (int oz = 0; oz < kRZ; ++oz) acc[oy][oz] = v4f{0.f, 0.f, 0.f, 0.f};
+    const uint16_t* inb = in + (size_t)b * N * 16 + 4 * g;
+    int xo[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) xo[q] = wrapn(iseg * 16 + m + q - 1, n);
+#pragma unroll
+    for (int iz = 0; iz < kRZ + 2; ++iz) {
+        const int kk = wrapn(k0 - 1 + iz, n);
+#pragma unroll
+        for (int iy = 0; iy < kRY + 2; ++iy) {
+            const size_t row = (size_t)n * ((size_t)wrapn(j0 - 1 + iy, n) + (size_t)n * kk);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {   // x shift dx = q - 1
+                const v4s a = *reinterpret_cast<const v4s*>(inb + (row + xo[q]) * 16);
+#pragma unroll
+                for (int oz = 0; oz < kRZ; ++oz) {
+                    const int dz = iz - 1 - oz;
+                    if (dz < -1 || dz > 1) continue;
+#pragma unroll
+                    for (int oy = 0; oy < kRY; ++oy) {
+                        const int dy = iy - 1 - oy;
+                        if (dy < -1 || dy > 1) continue;
+                        const int tap = (dz + 1) * 9 + (dy + 1) * 3 + q;
+                        acc[oy][oz] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, B[tap], acc[oy][oz], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    // lane holds D[4g + e][lane & 15] of each output row
+    const int nn = lane & 15;
+#pragma unroll
+    for (int oz = 0; oz < kRZ; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < kRY; ++oy)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const size_t cell = (size_t)(iseg * 16 + 4 * g + e) +
+                                    (size_t)n * ((size_t)(j0 + oy) + (size_t)n * (k0 + oz));
+                const size_t P = (size_t)b * N + cell;
+                float v = acc[oy][oz][e];
+                if (FINAL) {
+                    if (nn == 0) yout[P] = v * yscale;
+                } else {
+                    if (relu) v = v > 0.f ? v : 0.f;
+                    out[P * 16 + nn] = f2bf(v);
+                }
+            }
+}
+
 // Weight gradient of one layer: partial sums over this wavefront's cells of
 // D[co][(tap, ci)] = sum_cells g[cell][co] in[cell + d(tap)][ci], one 16x16 tile
 // per K-block, written to part[wave][kb][co][n].
@@ -288,21 +374,27 @@ static dim3 conv_grid(int n, int batch) {
     return dim3((unsigned)((waves + 3) / 4));
 }
 
+// Blocks of 4 wavefronts, one wavefront per 16 cells x kRY x kRZ output rows.
+static dim3 conv_rows_grid(int n, int batch) {
+    const long waves = (long)batch * (n / kRZ) * (n / kRY) * (n / 16);
+    return dim3((unsigned)((waves + 3) / 4));
+}
+
 void net_forward(hipStream_t s, int n, int batch, const void* wpk, const uint16_t* x4,
                  uint16_t* a, uint16_t* b, float* y, float yscale) {
     const v4s* p = reinterpret_cast<const v4s*>(wpk);
-    const dim3 G = conv_grid(n, batch), B(256);
+    const dim3 G = conv_grid(n, batch), GR = conv_rows_grid(n, batch), B(256);
     hipLaunchKernelGGL((k_conv<4, false>), G, B, 0, s, n, batch, x4, p, (const uint16_t*)nullptr, 1, a,
                        (float*)nullptr, 1.f);
     p += 7 * 64;
-    hipLaunchKernelGGL((k_conv<16, false>), G, B, 0, s, n, batch, a, p, (const uint16_t*)nullptr, 1, b,
-                       (float*)nullptr, 1.f);
+    hipLaunchKernelGGL((k_conv16_rows<false>), GR, B, 0, s, n, batch, a, p, 1, b, (float*)nullptr,
+                       1.f);
     p += 27 * 64;
-    hipLaunchKernelGGL((k_conv<16, false>), G, B, 0, s, n, batch, b, p, (const uint16_t*)nullptr, 1, a,
-                       (float*)nullptr, 1.f);
+    hipLaunchKernelGGL((k_conv16_rows<false>), GR, B, 0, s, n, batch, b, p, 1, a, (float*)nullptr,
+                       1.f);
     p += 27 * 64;
-    hipLaunchKernelGGL((k_conv<16, true>), G, B, 0, s, n, batch, a, p, (const uint16_t*)nullptr, 0,
-                       (uint16_t*)nullptr, y, yscale);
+    hipLaunchKernelGGL((k_conv16_rows<true>), GR, B, 0, s, n, batch, a, p, 0, (uint16_t*)nullptr, y,
+                       yscale);
 }
 
 // ---- training workspace ----

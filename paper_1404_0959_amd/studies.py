@@ -1,0 +1,128 @@
+"""Long runs of the step that report physics rather than throughput.
+
+    python -m paper_1404_0959_amd.studies precision [--n 256] [--steps 200]
+    python -m paper_1404_0959_amd.studies stats [--n 128] [--steps 500]
+
+precision: the FP32 mode (FP32 fields and inner CG, FP64 residual
+refinement, reductions and mass budget) against plain FP64 on the same seeded
+decaying-HIT case (Mach 0.2, one dust class at Stokes 0.2, pressure residual
+1e-6).  Every `every` steps the kinetic energy, enstrophy and particle
+concentration variance of both runs are compared.  Instantaneous fields of a
+turbulent flow decorrelate, so the differences are set beside the spread of a
+second FP64 run whose initial velocity is perturbed by 1e-7 (relative): the
+FP32 error is acceptable where it stays within a small multiple of that
+chaotic spread, with floors of 1e-5 (energy), 1e-4 (enstrophy) and 1e-3
+(concentration variance) relative.
+
+stats: the plain FP64 method at 128^3, Mach 0.5, three dust classes (Stokes
+0.05, 0.2, 0.5), adaptive dt at CFL 0.5, statistics every 10 steps: energy,
+enstrophy, density and Mach r.m.s., concentration variance per class and the
+gas and dust mass budgets.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import pisoc as P
+from .inputs import make_hit_case
+
+FLOORS = {"ke": 1e-5, "enstrophy": 1e-4, "conc_var": 1e-3}
+
+
+def _series(solver, steps, every):
+    out = [dict(step=0, t=solver.t, **solver.stats())]
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        st, info = solver.step(k)
+        if st < 0:
+            raise P.PisocError(st, solver.last_error())
+        done += k
+        out.append(dict(step=done, t=solver.t, iters=[i["pcg_iters"] for i in info], **solver.stats()))
+    return out
+
+
+def precision(n=256, steps=200, every=10, seed=0, p_tol=1e-6, inner_tol=1e-7, log=print):
+    case = make_hit_case(n, seed, mach=0.2, stokes=(0.2,))
+    kw = dict(p_tol=p_tol, cfl=0.5)
+    runs = {}
+    t0 = time.time()
+    runs["fp64"] = _series(P.Solver.from_case(case, **kw), steps, every)
+    log(f"fp64 done {time.time() - t0:.1f}s")
+    pert = make_hit_case(n, seed, mach=0.2, stokes=(0.2,))
+    rng = np.random.default_rng(seed + 1000)
+    pert.u = pert.u * (1.0 + 1e-7 * rng.standard_normal(pert.u.shape))
+    runs["fp64_perturbed"] = _series(P.Solver.from_case(pert, **kw), steps, every)
+    log(f"perturbed done {time.time() - t0:.1f}s")
+    runs["fp32"] = _series(P.Solver.from_case(case, precision=P.FP32_REFINED,
+                                              inner_tol=inner_tol, **kw), steps, every)
+    log(f"fp32 done {time.time() - t0:.1f}s")
+
+    def rel(a, b):
+        return abs(a - b) / abs(b) if b != 0 else abs(a - b)
+    rows = []
+    worst = {k: 0.0 for k in FLOORS}
+    for a, b, c in zip(runs["fp32"], runs["fp64"], runs["fp64_perturbed"]):
+        row = dict(step=b["step"], t=b["t"])
+        for key in FLOORS:
+            va = a[key][0] if key == "conc_var" else a[key]
+            vb = b[key][0] if key == "conc_var" else b[key]
+            vc = c[key][0] if key == "conc_var" else c[key]
+            err, spread = rel(va, vb), rel(vc, vb)
+            bound = max(3.0 * spread, FLOORS[key])
+            row[key] = dict(fp64=vb, fp32_rel_err=err, chaotic_spread=spread, bound=bound)
+            worst[key] = max(worst[key], err / bound)
+        rows.append(row)
+    mass = [abs(r["mass_gas"] - runs["fp32"][0]["mass_gas"]) / runs["fp32"][0]["mass_gas"]
+            for r in runs["fp32"]]
+    return dict(n=n, steps=steps, every=every, seed=seed, p_tol=p_tol, rows=rows,
+                worst_err_over_bound=worst, fp32_gas_mass_drift_max=max(mass),
+                t_end=runs["fp64"][-1]["t"])
+
+
+def stats_run(n=128, steps=500, every=10, seed=0, p_tol=1e-8, mach=0.5,
+              stokes=(0.05, 0.2, 0.5), log=print):
+    case = make_hit_case(n, seed, mach=mach, stokes=stokes)
+    s = P.Solver.from_case(case, p_tol=p_tol, cfl=0.5)
+    t0 = time.time()
+    series = _series(s, steps, every)
+    log(f"{steps} steps in {time.time() - t0:.1f}s")
+    m0 = series[0]["mass_gas"]
+    mp0 = series[0]["mass_p"]
+    drift = max(abs(r["mass_gas"] - m0) / m0 for r in series)
+    pdrift = max(abs(r["mass_p"][c] - mp0[c]) / mp0[c] for r in series for c in range(len(mp0)))
+    return dict(n=n, steps=steps, every=every, mach=mach, stokes=list(stokes), p_tol=p_tol,
+                series=[{k: v for k, v in r.items() if k != "iters"} for r in series],
+                mean_pcg_iters=float(np.mean([np.mean(i) for r in series[1:] for i in r["iters"]])),
+                gas_mass_drift_max=drift, dust_mass_drift_max=pdrift)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["precision", "stats"])
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--every", type=int, default=10)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+
+    def log(m):
+        print(m, file=sys.stderr, flush=True)
+    if args.what == "precision":
+        r = precision(n=args.n or 256, steps=args.steps or 200, every=args.every, log=log)
+    else:
+        r = stats_run(n=args.n or 128, steps=args.steps or 500, every=args.every, log=log)
+    text = json.dumps(r)
+    print(text)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+
+
+if __name__ == "__main__":
+    main()
