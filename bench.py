@@ -179,6 +179,36 @@ def ensemble_run(P, torch, args, weights):
     return out
 
 
+KERNEL_SOURCES = ("kernels.hip", "device.hpp", "launch.hpp", "net.hip")
+# dominant kernel class -> the 256^3 kernel whose HBM bytes the committed
+# counter summary holds
+TRAFFIC_NAME = {("k_pcg_spmv", "f32+f64"): "k_pcg_spmv_tiled<float>",
+                ("k_pcg_spmv", "f64"): "k_pcg_spmv_tiled<double>",
+                ("k_pcg_update", "f32+f64"): "k_pcg_update<float>",
+                ("k_pcg_update", "f64"): "k_pcg_update<double>"}
+
+
+def measured_traffic(kernel, dtype, n):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when it does not cover this kernel and size or the
+    kernel sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_256.json")
+    if n != 256 or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1404_0959_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    k = rec["kernels"].get(TRAFFIC_NAME.get((kernel, dtype), ""))
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+
+
 def roofline(prof):
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
     avg_ms = dom["ms"] / dom["launches"]
@@ -242,6 +272,8 @@ def main():
     head = modes[-1]
     H = runs[head]
     roof, kernels = roofline(H["prof"])
+    roof["traffic"] = measured_traffic(roof["kernel"], "f64" if head == "fp64" else "f32+f64",
+                                       args.n)
     log(json.dumps(kernels))
 
     ens = None

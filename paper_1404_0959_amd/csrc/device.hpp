@@ -118,6 +118,11 @@ __device__ inline R i4r(const T* __restrict__ q, const CellIdx& c, int d, int s)
     return (R(9) * (b + e) - (a + f)) * R(0.0625);
 }
 
+// Scheduling fence placed after a cell's gathered loads: the compiler may not
+// move the arithmetic that uses them above it, nor the loads below it, so all
+// of the cell's loads are in flight before the first wait.
+__device__ inline void loads_issued() { __builtin_amdgcn_sched_barrier(0); }
+
 // A field on the cross-shaped stencil of reach 2, gathered into registers so
 // that all of its loads are in flight together: v[0] is the cell, v[1 + 4d + t]
 // the cells -2, -1, +1, +2 (t = 0..3) steps along axis d.
@@ -144,6 +149,46 @@ template <typename T>
 __device__ inline T i4g(const T (&v)[13], int d, int s) {
     const T a = g13(v, d, s - 1), b = g13(v, d, s), e = g13(v, d, s + 1), f = g13(v, d, s + 2);
     return (T(9) * (b + e) - (a + f)) * T(0.0625);
+}
+
+// I4 of gathered values evaluated in the arithmetic of R (same operations as i4r).
+template <typename R, typename T>
+__device__ inline R i4gr(const T (&v)[13], int d, int s) {
+    const R a = (R)g13(v, d, s - 1), b = (R)g13(v, d, s), e = (R)g13(v, d, s + 1),
+            f = (R)g13(v, d, s + 2);
+    return (R(9) * (b + e) - (a + f)) * R(0.0625);
+}
+
+// Gauss-I4 cell derivative along d from gathered values (same operations as dgauss).
+template <typename T>
+__device__ inline T dgauss13(const T (&v)[13], int d, T inv_h) {
+    return (i4g(v, d, 0) - i4g(v, d, -1)) * inv_h;
+}
+
+// The cross of reach 1: v[0] the cell, v[1 + 2d] and v[2 + 2d] the cells -1
+// and +1 along axis d.
+template <typename T>
+__device__ inline void gather7(const T* __restrict__ q, const CellIdx& c, T (&v)[7]) {
+    v[0] = q[c.self()];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        v[1 + 2 * d] = q[c.sh(d, -1)];
+        v[2 + 2 * d] = q[c.sh(d, 1)];
+    }
+}
+
+// The five cells -2..2 along axis d: v[s + 2].
+template <typename T>
+__device__ inline void gather_line(const T* __restrict__ q, const CellIdx& c, int d, T (&v)[5]) {
+#pragma unroll
+    for (int s = -2; s <= 2; ++s) v[s + 2] = q[c.sh(d, s)];
+}
+
+// I4 onto face s + 1/2 along the gathered line (same operations as i4r).
+template <typename R, typename T>
+__device__ inline R i4l(const T (&v)[5], int s) {
+    const R a = (R)v[s + 1], b = (R)v[s + 2], e = (R)v[s + 3], f = (R)v[s + 4];
+    return (R(9) * (b + e) - (a + f)) * R(0.0625);
 }
 
 // Gauss-theorem cell derivative along d from I4 face values.

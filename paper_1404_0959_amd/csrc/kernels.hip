@@ -85,11 +85,18 @@ __global__ void __launch_bounds__(kBlock) k_cfl(Phys ph, const DevState* st, con
     const size_t N = ncell(ph);
     double v[1] = {0.0};
     FOR_CELLS(ph)
+    T fp[3], fm[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        fp[d] = phi[d * N + P];
+        fm[d] = phi[d * N + c.sh(d, -1)];
+    }
+    const T rP = r[P];
+    loads_issued();
     double f = 0.0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-        f += fabs((double)phi[d * N + P]) + fabs((double)phi[d * N + c.sh(d, -1)]);
-    double s = f / (2.0 * ((st + mem_)->rho_ref + (double)r[P]) * ph.V);
+    for (int d = 0; d < 3; ++d) f += fabs((double)fp[d]) + fabs((double)fm[d]);
+    double s = f / (2.0 * ((st + mem_)->rho_ref + (double)rP) * ph.V);
     v[0] = s > v[0] ? s : v[0];
     END_CELLS
     block_partials<1, 1u>(v, part);
@@ -156,9 +163,14 @@ __global__ void __launch_bounds__(kBlock) k_mom_source(Phys ph, const DevState* 
     const T dt = (T)(st + mem_)->dt;
     const T m3 = (T)(ph.mu / 3.0), inv_h = (T)ph.inv_h;
     FOR_CELLS(ph)
-    const T rho = (T)(st + mem_)->rho_ref + rn[P];
+    T dv[13], uv[3];
+    gather13(divu, c, dv);
 #pragma unroll
-    for (int m = 0; m < 3; ++m) s[m * N + P] = rho * un[m * N + P] / dt + m3 * dgauss(divu, c, m, inv_h);
+    for (int m = 0; m < 3; ++m) uv[m] = un[m * N + P];
+    const T rho = (T)(st + mem_)->rho_ref + rn[P];
+    loads_issued();
+#pragma unroll
+    for (int m = 0; m < 3; ++m) s[m * N + P] = rho * uv[m] / dt + m3 * dgauss13(dv, m, inv_h);
     END_CELLS
 }
 
@@ -191,6 +203,7 @@ __global__ void __launch_bounds__(kBlock) k_mom_sweep(Phys ph, const DevState* s
         sv[d] = s[d * N + P];
     }
     const T a = aP[P];
+    loads_issued();
     T dphi = T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) dphi += fp[d] - fm[d];
@@ -238,24 +251,33 @@ __global__ void __launch_bounds__(kBlock) k_corr_rhs(
     const double rref = (st + mem_)->rho_ref;
     double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
+    // every load of the cell first, then the FP64 arithmetic
+    T wv[13], rv[13], hl[3][5], pv[7];
+    gather13(w, c, wv);
+    gather13(rk, c, rv);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gather_line(hbya + d * N, c, d, hl[d]);
+    gather7(p0, c, pv);
+    const T rnP = rn[P];
+    loads_issued();
     double divF = 0.0, sumK = 0.0;
-    const double p0P = (double)p0[P];
+    const double p0P = (double)pv[0];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
 #pragma unroll
         for (int s = -1; s <= 0; ++s) {
-            const double Kf = i4r<double>(w, c, d, s);
-            const double ph_f = (rref + i4r<double>(rk, c, d, s)) * i4r<double>(hbya + d * N, c, d, s) * A;
-            const double sn = (s == 0 ? ((double)p0[c.sh(d, 1)] - p0P)
-                                      : (p0P - (double)p0[c.sh(d, -1)])) * inv_h;
+            const double Kf = i4gr<double>(wv, d, s);
+            const double ph_f = (rref + i4gr<double>(rv, d, s)) * i4l<double>(hl[d], s) * A;
+            const double sn = (s == 0 ? ((double)pv[2 + 2 * d] - p0P)
+                                      : (p0P - (double)pv[1 + 2 * d])) * inv_h;
             const double F = ph_f - Kf * A * sn;
             divF += s == 0 ? F : -F;
             sumK += Kf;
             if (s == 0) phiH[d * N + P] = (T)ph_f;
         }
     }
-    const double b = -(((double)rk[P] - (double)rn[P]) / dt + divF * inv_V);
-    const double rho = rref + (double)rk[P];
+    const double b = -(((double)rv[0] - (double)rnP) / dt + divF * inv_V);
+    const double rho = rref + (double)rv[0];
     const double psidt = rho / (ph.gamma * ((st + mem_)->p_ref + p0P)) / dt;
     const T dgT = (T)(psidt + sumK * inv_h2);
     const T bT = (T)b;
@@ -300,20 +322,28 @@ __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
     const double inv_h2 = ph.inv_h2;
     double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
-    auto xn = [&](size_t Q) { return x64[Q] + (double)d[Q]; };
-    const double xP = xn(P);
+    T wv[13], dv[7];
+    double xv[7];
+    gather13(w, c, wv);
+    gather7(x64, c, xv);
+    gather7(d, c, dv);
+    const double bP = b64[P];
+    const T dgP = diag[P];
+    loads_issued();
+    auto xn = [&](int t) { return xv[t] + (double)dv[t]; };
+    const double xP = xn(0);
     double lap = 0.0, sumK = 0.0;
 #pragma unroll
     for (int dd = 0; dd < 3; ++dd) {
-        const double kp = i4r<double>(w, c, dd, 0), km = i4r<double>(w, c, dd, -1);
-        lap += kp * (xP - xn(c.sh(dd, 1))) + km * (xP - xn(c.sh(dd, -1)));
+        const double kp = i4gr<double>(wv, dd, 0), km = i4gr<double>(wv, dd, -1);
+        lap += kp * (xP - xn(2 + 2 * dd)) + km * (xP - xn(1 + 2 * dd));
         sumK += kp + km;
     }
-    const double r = b64[P] - (((double)diag[P] - sumK * inv_h2) * xP + lap * inv_h2);
+    const double r = bP - (((double)dgP - sumK * inv_h2) * xP + lap * inv_h2);
     x64n[P] = xP;
     const T rT = (T)r;
     r32[P] = rT;
-    v[0] += (double)rT * ((double)rT / (double)diag[P]);
+    v[0] += (double)rT * ((double)rT / (double)dgP);
     v[1] += r * r;
     v[2] += r * r;
     END_CELLS
@@ -705,17 +735,23 @@ __global__ void __launch_bounds__(kBlock) k_guess_start(Phys ph, const DevState*
     const double s1 = (st + mem_)->red[6], inv_h2 = ph.inv_h2;
     double v[2] = {0.0, 0.0};
     FOR_CELLS(ph)
-    auto g = [&](size_t Q) { return s1 * (double)y[Q]; };
-    const double gP = g(P);
+    T wv[13];
+    float yv[7];
+    gather13(w, c, wv);
+    gather7(y, c, yv);
+    const T dgP = diag[P];
+    const double bP = b64 ? b64[P] : (double)b[P];
+    loads_issued();
+    auto g = [&](int t) { return s1 * (double)yv[t]; };
+    const double gP = g(0);
     double lap = 0.0, sumK = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double kp = i4r<double>(w, c, d, 0), km = i4r<double>(w, c, d, -1);
-        lap += kp * (gP - g(c.sh(d, 1))) + km * (gP - g(c.sh(d, -1)));
+        const double kp = i4gr<double>(wv, d, 0), km = i4gr<double>(wv, d, -1);
+        lap += kp * (gP - g(2 + 2 * d)) + km * (gP - g(1 + 2 * d));
         sumK += kp + km;
     }
-    const double Mg = ((double)diag[P] - sumK * inv_h2) * gP + lap * inv_h2;
-    const double bP = b64 ? b64[P] : (double)b[P];
+    const double Mg = ((double)dgP - sumK * inv_h2) * gP + lap * inv_h2;
     gout[P] = (T)gP;
     mg[P] = (T)Mg;
     v[0] += gP * bP;
@@ -806,15 +842,25 @@ __global__ void __launch_bounds__(kBlock) k_corr_flux(Phys ph, const T* __restri
     const size_t N = ncell(ph);
     const T A = (T)ph.A, inv_h = (T)ph.inv_h;
     FOR_CELLS(ph)
-    const T pP = p0[P] + x[P];
-    pt[P] = pP;
+    T wv[13], p0n[3], xn[3], hP[3];
+    gather13(w, c, wv);
+    const T p0P = p0[P], xP = x[P];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const size_t Q = c.sh(d, 1);
-        const T pQ = p0[Q] + x[Q];
-        phik[d * N + P] = phiH[d * N + P] - i4(w, c, d, 0) * A * (pQ - pP) * inv_h;
+        p0n[d] = p0[Q];
+        xn[d] = x[Q];
+        hP[d] = phiH[d * N + P];
     }
-    if (snap_x) snap_x[P] = (double)x[P];
+    loads_issued();
+    const T pP = p0P + xP;
+    pt[P] = pP;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T pQ = p0n[d] + xn[d];
+        phik[d * N + P] = hP[d] - i4g(wv, d, 0) * A * (pQ - pP) * inv_h;
+    }
+    if (snap_x) snap_x[P] = (double)xP;
     END_CELLS
 }
 
@@ -835,16 +881,25 @@ __global__ void __launch_bounds__(kBlock) k_corr_update(Phys ph, const DevState*
     const T inv_V = (T)ph.inv_V, inv_h = (T)ph.inv_h;
     double v[3] = {0.0, 0.0, -__builtin_inf()};
     FOR_CELLS(ph)
+    T fp[3], fm[3], hb[3], pv[13];
+    gather13(pt, c, pv);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        fp[d] = phik[d * N + P];
+        fm[d] = phik[d * N + c.sh(d, -1)];
+        hb[d] = hbya[d * N + P];
+    }
+    const T rnP = rn[P], a = aP[P];
+    loads_issued();
     T dphi = T(0);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) dphi += phik[d * N + P] - phik[d * N + c.sh(d, -1)];
-    const T r = rn[P] - dt * dphi * inv_V;
+    for (int d = 0; d < 3; ++d) dphi += fp[d] - fm[d];
+    const T r = rnP - dt * dphi * inv_V;
     rk[P] = r;
-    const T a = aP[P];
     double usq = 0.0;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        const T um = hbya[m * N + P] - dgauss(pt, c, m, inv_h) / a;
+        const T um = hb[m] - dgauss13(pv, m, inv_h) / a;
         u[m * N + P] = um;
         usq += (double)um * (double)um;
     }
@@ -868,13 +923,19 @@ __global__ void __launch_bounds__(kBlock) k_dudt(Phys ph, const DevState* st,
     const size_t N = ncell(ph);
     const T dt = (T)(st + mem_)->dt, inv_h = (T)ph.inv_h;
     FOR_CELLS(ph)
-    const T ux = u1[P], uy = u1[N + P], uz = u1[2 * N + P];
+    T uv[3][13], u0[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        const T* q = u1 + m * N;
-        const T conv = ux * dgauss(q, c, 0, inv_h) + uy * dgauss(q, c, 1, inv_h) +
-                       uz * dgauss(q, c, 2, inv_h);
-        acc[m * N + P] = (q[P] - un[m * N + P]) / dt + conv;
+        gather13(u1 + m * N, c, uv[m]);
+        u0[m] = un[m * N + P];
+    }
+    loads_issued();
+    const T ux = uv[0][0], uy = uv[1][0], uz = uv[2][0];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const T conv = ux * dgauss13(uv[m], 0, inv_h) + uy * dgauss13(uv[m], 1, inv_h) +
+                       uz * dgauss13(uv[m], 2, inv_h);
+        acc[m * N + P] = (uv[m][0] - u0[m]) / dt + conv;
     }
     END_CELLS
 }
@@ -891,10 +952,19 @@ __global__ void __launch_bounds__(kBlock) k_dust_flux(Phys ph, const DevState* s
     const size_t N = ncell(ph);
     const T A = (T)ph.A, t = (T)(st + mem_)->tau[cls], rref = (T)(st + mem_)->rho_ref;
     FOR_CELLS(ph)
+    T rv[13], al[3][5], fv[3];
+    gather13(r1, c, rv);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        gather_line(acc + d * N, c, d, al[d]);
+        fv[d] = phi[d * N + P];
+    }
+    const T rj = rhoj[P], rnP = rn[P];
+    loads_issued();
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-        G[d * N + P] = phi[d * N + P] - t * (rref + i4(r1, c, d, 0)) * i4(acc + d * N, c, d, 0) * A;
-    Y[P] = rhoj[P] / (rref + rn[P]);
+        G[d * N + P] = fv[d] - t * (rref + i4g(rv, d, 0)) * i4l<T>(al[d], 0) * A;
+    Y[P] = rj / (rref + rnP);
     END_CELLS
 }
 
@@ -910,17 +980,26 @@ __global__ void __launch_bounds__(kBlock) k_dust_sweep(Phys ph, const DevState* 
     const size_t N = ncell(ph);
     const T dt = (T)(st + mem_)->dt, inv_V = (T)ph.inv_V;
     FOR_CELLS(ph)
+    T yv[13], gpv[3], gmv[3];
+    gather13(Yin, c, yv);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        gpv[d] = G[d * N + P];
+        gmv[d] = G[d * N + c.sh(d, -1)];
+    }
+    const T rj = rhoj[P], r1P = r1[P];
+    loads_issued();
     T conv = T(0), dG = T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const T gp = G[d * N + P], gm = G[d * N + c.sh(d, -1)];
-        conv += gp * i4(Yin, c, d, 0) - gm * i4(Yin, c, d, -1);
+        const T gp = gpv[d], gm = gmv[d];
+        conv += gp * i4g(yv, d, 0) - gm * i4g(yv, d, -1);
         dG += gp - gm;
     }
     conv *= inv_V;
     dG *= inv_V;
-    const T off = conv - T(0.5625) * dG * Yin[P];
-    Yout[P] = (rhoj[P] / dt - off) / (((T)(st + mem_)->rho_ref + r1[P]) / dt + T(0.5625) * dG);
+    const T off = conv - T(0.5625) * dG * yv[0];
+    Yout[P] = (rj / dt - off) / (((T)(st + mem_)->rho_ref + r1P) / dt + T(0.5625) * dG);
     END_CELLS
 }
 
