@@ -180,6 +180,30 @@ __global__ void __launch_bounds__(kBlock) k_mom_source(Phys ph, const DevState* 
 // stores w = rho_k / a_P and p_dev(rho_k) of the current density iterate.
 // N(u) = (1/V) sum_f phi_f^out I4(u)_f - (9/16) div(phi) u_P - mu sum_nb u_nb / h^2.
 template <typename T, bool HBYA>
+__device__ inline void mom_cell(const T (&u)[3][13], const T (&pv)[13], const T (&fp)[3],
+                                const T (&fm)[3], const T (&sv)[3], T a, T inv_V, T inv_h,
+                                T mu_h2, T (&out)[3], T& ia) {
+    T dphi = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dphi += fp[d] - fm[d];
+    dphi *= inv_V;
+    ia = T(1) / a;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        T conv = T(0), nb = T(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            conv += fp[d] * i4g(u[m], d, 0) - fm[d] * i4g(u[m], d, -1);
+            nb += g13(u[m], d, 1) + g13(u[m], d, -1);
+        }
+        T off = conv * inv_V - T(0.5625) * dphi * u[m][0] - mu_h2 * nb;
+        T rhs = sv[m] - off;
+        if (!HBYA) rhs -= (i4g(pv, m, 0) - i4g(pv, m, -1)) * inv_h;
+        out[m] = rhs * ia;
+    }
+}
+
+template <typename T, bool HBYA>
 __global__ void __launch_bounds__(kBlock) k_mom_sweep(Phys ph, const DevState* st, const T* __restrict__ uin,
                                                       T* __restrict__ uout, const T* __restrict__ phi,
                                                       const T* __restrict__ aP, const T* __restrict__ s,
@@ -203,30 +227,212 @@ __global__ void __launch_bounds__(kBlock) k_mom_sweep(Phys ph, const DevState* s
         sv[d] = s[d * N + P];
     }
     const T a = aP[P];
+    const T rkP = HBYA ? rk[P] : T(0);
     loads_issued();
-    T dphi = T(0);
+    T out[3], ia;
+    mom_cell<T, HBYA>(u, pv, fp, fm, sv, a, inv_V, inv_h, mu_h2, out, ia);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) dphi += fp[d] - fm[d];
-    dphi *= inv_V;
-    const T ia = T(1) / a;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        T conv = T(0), nb = T(0);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            conv += fp[d] * i4g(u[m], d, 0) - fm[d] * i4g(u[m], d, -1);
-            nb += g13(u[m], d, 1) + g13(u[m], d, -1);
-        }
-        T off = conv * inv_V - T(0.5625) * dphi * u[m][0] - mu_h2 * nb;
-        T rhs = sv[m] - off;
-        if (!HBYA) rhs -= (i4g(pv, m, 0) - i4g(pv, m, -1)) * inv_h;
-        uout[m * N + P] = rhs * ia;
-    }
+    for (int m = 0; m < 3; ++m) uout[m * N + P] = out[m];
     if (HBYA) {
-        w[P] = ((T)(st + mem_)->rho_ref + rk[P]) * ia;
-        p0[P] = pdev(rk[P], (st + mem_)->rho_ref, (st + mem_)->p_ref, ph.gamma);
+        w[P] = ((T)(st + mem_)->rho_ref + rkP) * ia;
+        p0[P] = pdev(rkP, (st + mem_)->rho_ref, (st + mem_)->p_ref, ph.gamma);
     }
     END_CELLS
+}
+
+// The same sweep as a z-march over a 64 x 8 column tile (n a multiple of 64,
+// n >= 128): each velocity component and p^n are read once per cell from HBM;
+// their x-y neighbours of the current plane come from LDS tiles (halo 2), the
+// z neighbours from five-plane register queues; the fluxes phi_x, phi_y of the
+// plane sit in LDS with the one low-side neighbour each needs, phi_z in a
+// two-plane queue.  All loads of plane k + 1 (queue heads, own-cell values and
+// this thread's share of the halo) are issued before plane k's LDS-only
+// barriers.  The per-cell arithmetic is mom_cell, as in k_mom_sweep.
+template <typename T, bool HBYA>
+__global__ void __launch_bounds__(kTX * kTY) k_mom_sweep_tiled(
+    Phys ph, const DevState* st, const T* __restrict__ uin, T* __restrict__ uout,
+    const T* __restrict__ phi, const T* __restrict__ aP, const T* __restrict__ s,
+    const T* __restrict__ pn, const T* __restrict__ rk, T* __restrict__ w, T* __restrict__ p0) {
+    MEMBER(ph)
+    const size_t N = ncell(ph);
+    const T inv_V = (T)ph.inv_V, inv_h = (T)ph.inv_h;
+    const T mu_h2 = (T)(ph.mu * ph.inv_h2);
+    const int n = ph.n, cz = ph.cz;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kTX * ty;
+    const int i0 = bp_.x * kTX, j0 = bp_.y * kTY;
+    const int k0 = bz_ * cz;
+    const int k1 = k0 + cz < n ? k0 + cz : n;
+    const size_t nn = (size_t)n * n;
+    constexpr int NF = HBYA ? 3 : 4;            // fields with a halo-2 tile: u_x, u_y, u_z, p^n
+    constexpr int kHalo = 4 * kTX + 4 * kTY;    // halo cells of one such tile
+    constexpr int kJobs = NF * kHalo + kTY + kTX;
+    constexpr int kPer = (kJobs + kTX * kTY - 1) / (kTX * kTY);
+    // one LDS array (so that every store to it is an LDS store): the halo-2
+    // tiles of u_x, u_y, u_z (and p^n), phi_x at x = i0 - 1 .. i0 + 63, phi_y at
+    // y = j0 - 1 .. j0 + 7, and a scratch slot per thread for idle halo jobs
+    constexpr int kUW = kTX + 4, kUS = (kTY + 4) * kUW;
+    constexpr int kFX = NF * kUS, kFY = kFX + kTY * (kTX + 1), kDum = kFY + (kTY + 1) * kTX;
+    __shared__ T lds[kDum + kTX * kTY];
+    auto U = [&](int f, int y, int x) -> T& { return lds[f * kUS + y * kUW + x]; };
+    auto FX = [&](int y, int x) -> T& { return lds[kFX + y * (kTX + 1) + x]; };
+    auto FY = [&](int y, int x) -> T& { return lds[kFY + y * kTX + x]; };
+    auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
+    const size_t col = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty);
+    // this thread's halo jobs: source array, offset within a plane, LDS slot
+    typedef const T __attribute__((address_space(1)))* gptr;   // global memory
+    gptr hsrc[kPer];
+    size_t hoff[kPer];
+    int hdst[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int jb = tid + q * kTX * kTY;
+        hsrc[q] = (gptr)uin;
+        hoff[q] = col;
+        hdst[q] = kDum + tid;
+        if (jb < NF * kHalo) {
+            const int f = jb / kHalo, h = jb - f * kHalo;
+            const gptr src = (gptr)(f < 3 ? uin + (size_t)f * N : pn);
+            if (h < 4 * kTX) {                  // rows j0-2, j0-1, j0+8, j0+9
+                const int row = h / kTX, x = h - row * kTX;
+                const int yy = row < 2 ? row : kTY + row;
+                hsrc[q] = src;
+                hoff[q] = base_ + (size_t)(i0 + x) + (size_t)n * wr(j0 - 2 + yy);
+                hdst[q] = f * kUS + yy * kUW + x + 2;
+            } else {                            // columns i0-2, i0-1, i0+64, i0+65
+                const int t = h - 4 * kTX, c4 = t / kTY, y = t - c4 * kTY;
+                const int xx = c4 < 2 ? c4 : kTX + c4;
+                hsrc[q] = src;
+                hoff[q] = base_ + (size_t)wr(i0 - 2 + xx) + (size_t)n * (j0 + y);
+                hdst[q] = f * kUS + (y + 2) * kUW + xx;
+            }
+        } else if (jb < NF * kHalo + kTY) {     // phi_x at x = i0 - 1
+            const int y = jb - NF * kHalo;
+            hsrc[q] = (gptr)phi;
+            hoff[q] = base_ + (size_t)wr(i0 - 1) + (size_t)n * (j0 + y);
+            hdst[q] = kFX + y * (kTX + 1);
+        } else if (jb < kJobs) {                // phi_y at y = j0 - 1
+            const int x = jb - NF * kHalo - kTY;
+            hsrc[q] = (gptr)(phi + N);
+            hoff[q] = base_ + (size_t)(i0 + x) + (size_t)n * wr(j0 - 1);
+            hdst[q] = kFY + x;
+        }
+    }
+    // queues and the values of the first plane
+    T uq[3][5], pq[5], fzq[2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int t = 0; t < 5; ++t) uq[m][t] = uin[(size_t)m * N + col + nn * wr(k0 - 2 + t)];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) pq[t] = HBYA ? T(0) : pn[col + nn * wr(k0 - 2 + t)];
+    fzq[0] = phi[2 * N + col + nn * wr(k0 - 1)];
+    fzq[1] = phi[2 * N + col + nn * k0];
+    T cfx = phi[col + nn * k0], cfy = phi[N + col + nn * k0], ca = aP[col + nn * k0];
+    T cs[3], crk = HBYA ? rk[col + nn * k0] : T(0), ch[kPer];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) cs[m] = s[(size_t)m * N + col + nn * k0];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) ch[q] = hsrc[q][nn * (size_t)k0 + hoff[q]];
+    // values of plane k0 + 1 and the queue head at k0 + 3, rotated in after plane k0
+    T nu[3], np = T(0), nfz, nfx, nfy, na, ns[3], nrk = T(0), nh[kPer];
+    auto prefetch = [&](int kq, int kv) {      // queue head at plane kq, values at plane kv
+        const size_t pq3 = nn * (size_t)wr(kq), pv = nn * (size_t)wr(kv);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) nu[m] = uin[(size_t)m * N + col + pq3];
+        if (!HBYA) np = pn[col + pq3];
+        nfz = phi[2 * N + col + pv];
+        nfx = phi[col + pv];
+        nfy = phi[N + col + pv];
+        na = aP[col + pv];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) ns[m] = s[(size_t)m * N + col + pv];
+        if (HBYA) nrk = rk[col + pv];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) nh[q] = hsrc[q][pv + hoff[q]];
+    };
+    prefetch(k0 + 3, k0 + 1);
+    for (int kk = k0; kk < k1; ++kk) {
+        const size_t pl = nn * (size_t)kk;
+        // plane kk into LDS
+#pragma unroll
+        for (int m = 0; m < 3; ++m) U(m, ty + 2, tx + 2) = uq[m][2];
+        if (!HBYA) U(NF - 1, ty + 2, tx + 2) = pq[2];
+        FX(ty, tx + 1) = cfx;
+        FY(ty + 1, tx) = cfy;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) lds[hdst[q]] = ch[q];
+        lds_barrier();
+        T u[3][13], pv[13], fp[3], fm[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            u[m][0] = uq[m][2];
+            u[m][1] = U(m, ty + 2, tx);
+            u[m][2] = U(m, ty + 2, tx + 1);
+            u[m][3] = U(m, ty + 2, tx + 3);
+            u[m][4] = U(m, ty + 2, tx + 4);
+            u[m][5] = U(m, ty, tx + 2);
+            u[m][6] = U(m, ty + 1, tx + 2);
+            u[m][7] = U(m, ty + 3, tx + 2);
+            u[m][8] = U(m, ty + 4, tx + 2);
+            u[m][9] = uq[m][0];
+            u[m][10] = uq[m][1];
+            u[m][11] = uq[m][3];
+            u[m][12] = uq[m][4];
+        }
+        if (!HBYA) {
+            constexpr int f = NF - 1;
+            pv[0] = pq[2];
+            pv[1] = U(f, ty + 2, tx);
+            pv[2] = U(f, ty + 2, tx + 1);
+            pv[3] = U(f, ty + 2, tx + 3);
+            pv[4] = U(f, ty + 2, tx + 4);
+            pv[5] = U(f, ty, tx + 2);
+            pv[6] = U(f, ty + 1, tx + 2);
+            pv[7] = U(f, ty + 3, tx + 2);
+            pv[8] = U(f, ty + 4, tx + 2);
+            pv[9] = pq[0];
+            pv[10] = pq[1];
+            pv[11] = pq[3];
+            pv[12] = pq[4];
+        }
+        fp[0] = FX(ty, tx + 1);
+        fm[0] = FX(ty, tx);
+        fp[1] = FY(ty + 1, tx);
+        fm[1] = FY(ty, tx);
+        fp[2] = fzq[1];
+        fm[2] = fzq[0];
+        T out[3], ia;
+        mom_cell<T, HBYA>(u, pv, fp, fm, cs, ca, inv_V, inv_h, mu_h2, out, ia);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) uout[(size_t)m * N + col + pl] = out[m];
+        if (HBYA) {
+            w[col + pl] = ((T)(st + mem_)->rho_ref + crk) * ia;
+            p0[col + pl] = pdev(crk, (st + mem_)->rho_ref, (st + mem_)->p_ref, ph.gamma);
+        }
+        lds_barrier();
+        // advance the queues with the values loaded one plane ago, then load
+        // the queue head at kk + 4 and the values of plane kk + 2
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) uq[m][t] = uq[m][t + 1];
+            uq[m][4] = nu[m];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) pq[t] = pq[t + 1];
+        pq[4] = np;
+        fzq[0] = fzq[1];
+        fzq[1] = nfz;
+        cfx = nfx;
+        cfy = nfy;
+        ca = na;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) cs[m] = ns[m];
+        crk = nrk;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) ch[q] = nh[q];
+        prefetch(kk + 4, kk + 2);
+    }
 }
 
 // Corrector set-up: predicted fluxes phiH = I4(rho_k) I4(HbyA_d) A on the
@@ -1327,18 +1533,34 @@ void Ops<T>::mom_source(const Launch& L, hipStream_t s, const Phys& ph, const De
     LAUNCH(k_mom_source<T>, L, s, ph, st, rn, un, divu, src);
 }
 template <typename T>
-void Ops<T>::mom_sweep(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                       const T* uin, T* uout, const T* phi, const T* aP, const T* src,
-                       const T* pn) {
-    LAUNCH((k_mom_sweep<T, false>), L, s, ph, st, uin, uout, phi, aP, src, pn, (const T*)nullptr,
-           (T*)nullptr, (T*)nullptr);
+void Ops<T>::mom_sweep(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                       const DevState* st, const T* uin, T* uout, const T* phi, const T* aP,
+                       const T* src, const T* pn) {
+    if (TL.nblocks) {
+        Phys pt = ph;
+        pt.cz = TL.cz;
+        pt.nz = TL.nz;
+        LAUNCH((k_mom_sweep_tiled<T, false>), TL, s, pt, st, uin, uout, phi, aP, src, pn,
+               (const T*)nullptr, (T*)nullptr, (T*)nullptr);
+    } else {
+        LAUNCH((k_mom_sweep<T, false>), L, s, ph, st, uin, uout, phi, aP, src, pn,
+               (const T*)nullptr, (T*)nullptr, (T*)nullptr);
+    }
 }
 template <typename T>
-void Ops<T>::hbya(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                  const T* uin, T* hb, const T* phi, const T* aP, const T* src, const T* rk, T* w,
-                  T* p0) {
-    LAUNCH((k_mom_sweep<T, true>), L, s, ph, st, uin, hb, phi, aP, src, (const T*)nullptr, rk, w,
-           p0);
+void Ops<T>::hbya(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                  const DevState* st, const T* uin, T* hb, const T* phi, const T* aP,
+                  const T* src, const T* rk, T* w, T* p0) {
+    if (TL.nblocks) {
+        Phys pt = ph;
+        pt.cz = TL.cz;
+        pt.nz = TL.nz;
+        LAUNCH((k_mom_sweep_tiled<T, true>), TL, s, pt, st, uin, hb, phi, aP, src,
+               (const T*)nullptr, rk, w, p0);
+    } else {
+        LAUNCH((k_mom_sweep<T, true>), L, s, ph, st, uin, hb, phi, aP, src, (const T*)nullptr, rk,
+               w, p0);
+    }
 }
 template <typename T>
 void Ops<T>::corr_rhs(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, const T* rn,

@@ -62,12 +62,13 @@ struct Ops {
                         T* divu, T* pn);
     static void mom_source(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                            const T* rn, const T* un, const T* divu, T* src);
-    static void mom_sweep(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                          const T* uin, T* uout, const T* phi, const T* aP, const T* src,
-                          const T* pn);
-    static void hbya(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                     const T* uin, T* hb, const T* phi, const T* aP, const T* src, const T* rk,
-                     T* w, T* p0);
+    // TL: tiled launch (used when TL.nblocks > 0)
+    static void mom_sweep(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                          const DevState* st, const T* uin, T* uout, const T* phi, const T* aP,
+                          const T* src, const T* pn);
+    static void hbya(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                     const DevState* st, const T* uin, T* hb, const T* phi, const T* aP,
+                     const T* src, const T* rk, T* w, T* p0);
     static void corr_rhs(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                          const T* rn, const T* rk, const T* w, const T* hb, const T* p0, T* phiH,
                          T* r, T* x, T* diag, double* part_u, double* snap_b, double* snap_diag,

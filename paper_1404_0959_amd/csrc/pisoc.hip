@@ -466,7 +466,7 @@ void enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S) {
     for (int i = 0; i < p.n_mom_sweeps; ++i) {
         T* uout = (i & 1) ? S.ub : S.ua;
         timed(ctx, KC_MOM_SWEEP, 14, -1,
-              [&] { O::mom_sweep(L, s, ph, st, uin, uout, S.phin, S.aP, S.src, S.pn); });
+              [&] { O::mom_sweep(L, ctx->TL, s, ph, st, uin, uout, S.phin, S.aP, S.src, S.pn); });
         uin = uout;
     }
 }
@@ -484,7 +484,7 @@ void enqueue_corr_setup(pisoc_ctx* ctx, StepPtrs<T>& S, int corr, bool guess) {
     const bool f32 = sizeof(T) == sizeof(float);
     T* ucur = ucur_of(ctx, S);
     timed(ctx, KC_HBYA, 16, -1,
-          [&] { O::hbya(L, s, ph, ctx->st, ucur, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0); });
+          [&] { O::hbya(L, ctx->TL, s, ph, ctx->st, ucur, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0); });
     const bool cap = S.snap && corr == 0;
     timed(ctx, KC_CORR_RHS, f32 ? 17 : 13, -1, [&] {
         O::corr_rhs(L, s, ph, ctx->st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH, S.r, S.x, S.dg,
@@ -1106,8 +1106,8 @@ void enqueue_probe(pisoc_ctx* ctx) {
     const Launch& L = ctx->L;
     hipStream_t s = ctx->stream;
     DevState* st = ctx->st;
-    O::mom_sweep(L, s, ph, st, S.un, S.ua, S.phin, S.aP, S.src, S.pn);
-    O::hbya(L, s, ph, st, S.ua, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0);
+    O::mom_sweep(L, ctx->TL, s, ph, st, S.un, S.ua, S.phin, S.aP, S.src, S.pn);
+    O::hbya(L, ctx->TL, s, ph, st, S.ua, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0);
     O::corr_rhs(L, s, ph, st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH, S.r, S.x, S.dg, ctx->part(PS_U),
                 nullptr, nullptr, nullptr, S.b64, S.x64a);
     // two CG iterations that cannot stop early (tolerance 0, maxit above 2)
