@@ -641,7 +641,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(Phys ph, DevState* st, int 
 // K = I4(w) and the direction p = z + beta p_old are read once per cell from
 // HBM: the x-y neighbours of the current plane come from LDS tiles (halo 2 for
 // w, 1 for p), the z neighbours from per-thread register queues.
-template <typename T>
+template <typename T, int RPT>
 __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     Phys ph, DevState* st, int k, const T* __restrict__ r, const T* __restrict__ diag,
     const T* __restrict__ w, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ q,
@@ -675,46 +675,60 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     const bool first = k == 0;
     const T inv_h2 = (T)ph.inv_h2;
     const int n = ph.n, cz = ph.cz;
+    constexpr int TY = kTY * RPT;               // tile rows; thread row ty owns rows ty + e kTY
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kTX * ty;
-    const int i0 = bp_.x * kTX, j0 = bp_.y * kTY;
+    const int i0 = bp_.x * kTX, j0 = bp_.y * TY;
     const int k0 = bz_ * cz;
     const int k1 = k0 + cz < n ? k0 + cz : n;
     const size_t nn = (size_t)n * n;
-    __shared__ T ws[kTY + 4][kTX + 4];
-    __shared__ T ps[kTY + 2][kTX + 2];
+    __shared__ T ws[TY + 4][kTX + 4];
+    __shared__ T ps[TY + 2][kTX + 2];
     auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
     auto dirv = [&](size_t Q) -> T {
         const T zz = r[Q] / diag[Q];
         return first ? zz : zz + beta * pold[Q];
     };
-    const size_t col = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty);
-    T wq0 = w[col + nn * wr(k0 - 2)], wq1 = w[col + nn * wr(k0 - 1)], wq2 = w[col + nn * k0],
-      wq3 = w[col + nn * wr(k0 + 1)];
-    T pm = dirv(col + nn * wr(k0 - 1)), pc = dirv(col + nn * k0);
-    T dc = diag[col + nn * k0];
-    // this thread's halo cell, if any (same x-y position on every plane)
+    size_t col[RPT];
+    T wq0[RPT], wq1[RPT], wq2[RPT], wq3[RPT], wq4[RPT], pm[RPT], pc[RPT], dc[RPT];
+    T rn1[RPT], dn1[RPT], on1[RPT];
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+        col[e] = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty + e * kTY);
+        wq0[e] = w[col[e] + nn * wr(k0 - 2)];
+        wq1[e] = w[col[e] + nn * wr(k0 - 1)];
+        wq2[e] = w[col[e] + nn * k0];
+        wq3[e] = w[col[e] + nn * wr(k0 + 1)];
+        pm[e] = dirv(col[e] + nn * wr(k0 - 1));
+        pc[e] = dirv(col[e] + nn * k0);
+        dc[e] = diag[col[e] + nn * k0];
+    }
+    // this thread's halo cell, if any (same x-y position on every plane):
+    // w rows j0-2, j0-1, j0+TY, j0+TY+1; w columns i0-2, i0-1, i0+64, i0+65;
+    // p rows j0-1, j0+TY; p columns i0-1, i0+64
+    constexpr int nWR = 4 * kTX, nWC = 4 * TY, nPR = 2 * kTX, nPC = 2 * TY;
+    static_assert(nWR + nWC + nPR + nPC <= kTX * kTY, "one halo cell per thread");
     int hkind = 0, hy = 0, hx = 0;
     size_t hoff = 0;
-    if (tid < 256) {            // w rows j0-2, j0-1, j0+8, j0+9
-        const int row = tid >> 6, x = tid & 63;
-        hy = row < 2 ? row : kTY + row;
+    if (tid < nWR) {
+        const int row = tid / kTX, x = tid - row * kTX;
+        hy = row < 2 ? row : TY + row;
         hx = x + 2;
         hoff = base_ + (size_t)(i0 + x) + (size_t)n * wr(j0 - 2 + hy);
         hkind = 1;
-    } else if (tid < 288) {     // w columns i0-2, i0-1, i0+64, i0+65
-        const int t2 = tid - 256, c4 = t2 >> 3, y = t2 & 7;
+    } else if (tid < nWR + nWC) {
+        const int t2 = tid - nWR, c4 = t2 / TY, y = t2 - c4 * TY;
         hx = c4 < 2 ? c4 : kTX + c4;
         hy = y + 2;
         hoff = base_ + (size_t)wr(i0 - 2 + hx) + (size_t)n * (j0 + y);
         hkind = 1;
-    } else if (tid < 416) {     // p rows j0-1, j0+8
-        const int t3 = tid - 288, row = t3 >> 6, x = t3 & 63;
-        hy = row == 0 ? 0 : kTY + 1;
+    } else if (tid < nWR + nWC + nPR) {
+        const int t3 = tid - nWR - nWC, row = t3 / kTX, x = t3 - row * kTX;
+        hy = row == 0 ? 0 : TY + 1;
         hx = x + 1;
         hoff = base_ + (size_t)(i0 + x) + (size_t)n * wr(j0 - 1 + hy);
         hkind = 2;
-    } else if (tid < 432) {     // p columns i0-1, i0+64
-        const int t4 = tid - 416, c2 = t4 >> 3, y = t4 & 7;
+    } else if (tid < nWR + nWC + nPR + nPC) {
+        const int t4 = tid - nWR - nWC - nPR, c2 = t4 / TY, y = t4 - c2 * TY;
         hx = c2 == 0 ? 0 : kTX + 1;
         hy = y + 1;
         hoff = base_ + (size_t)wr(i0 - 1 + hx) + (size_t)n * (j0 + y);
@@ -726,61 +740,84 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     // Every load is unconditional and in bounds (threads without a halo cell
     // read their own), so no branch forces the loads to drain early.
     const T* hsrc = hkind == 1 ? w : r;                 // w halo, or r of the p halo
-    const size_t hq = hkind == 0 ? col : hoff;          // plane offset added per plane
+    const size_t hq = hkind == 0 ? col[0] : hoff;       // plane offset added per plane
     auto sel = [&](T v) { return first ? T(0) : v; };
-    T wq4 = w[col + nn * wr(k0 + 2)];
-    T rn1 = r[col + nn * wr(k0 + 1)], dn1 = diag[col + nn * wr(k0 + 1)];
-    T on1 = pold[col + nn * wr(k0 + 1)];   // raw; the select is applied at its use
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+        wq4[e] = w[col[e] + nn * wr(k0 + 2)];
+        rn1[e] = r[col[e] + nn * wr(k0 + 1)];
+        dn1[e] = diag[col[e] + nn * wr(k0 + 1)];
+        on1[e] = pold[col[e] + nn * wr(k0 + 1)];   // raw; the select is applied at its use
+    }
     T ha = hsrc[nn * (size_t)k0 + hq], hd = diag[nn * (size_t)k0 + hq];
     T ho = pold[nn * (size_t)k0 + hq];
     double acc = 0.0;
     for (int kk = k0; kk < k1; ++kk) {
         const size_t pl = nn * (size_t)kk;
-        const T wq4c = wq4, dn = dn1;
-        const T pp = rn1 / dn1 + beta * sel(on1);
+        T wq4c[RPT], dn[RPT], pp[RPT];
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) {
+            wq4c[e] = wq4[e];
+            dn[e] = dn1[e];
+            pp[e] = rn1[e] / dn1[e] + beta * sel(on1[e]);
+        }
         const T hwc = ha, hpc = ha / hd + beta * sel(ho);
         {
-            const size_t Qf = col + nn * wr(kk + 2);
             const size_t Hf = nn * (size_t)wr(kk + 1) + hq;
-            wq4 = w[col + nn * wr(kk + 3)];
-            rn1 = r[Qf];
-            dn1 = diag[Qf];
-            on1 = pold[Qf];
+#pragma unroll
+            for (int e = 0; e < RPT; ++e) {
+                const size_t Qf = col[e] + nn * wr(kk + 2);
+                wq4[e] = w[col[e] + nn * wr(kk + 3)];
+                rn1[e] = r[Qf];
+                dn1[e] = diag[Qf];
+                on1[e] = pold[Qf];
+            }
             ha = hsrc[Hf];
             hd = diag[Hf];
             ho = pold[Hf];
         }
-        ws[ty + 2][tx + 2] = wq2;
-        ps[ty + 1][tx + 1] = pc;
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) {
+            ws[ty + e * kTY + 2][tx + 2] = wq2[e];
+            ps[ty + e * kTY + 1][tx + 1] = pc[e];
+        }
         if (hkind == 1) ws[hy][hx] = hwc;
         else if (hkind == 2) ps[hy][hx] = hpc;
         lds_barrier();
-        const T kxp = (T(9) * (ws[ty + 2][tx + 2] + ws[ty + 2][tx + 3]) -
-                       (ws[ty + 2][tx + 1] + ws[ty + 2][tx + 4])) * T(0.0625);
-        const T kxm = (T(9) * (ws[ty + 2][tx + 1] + ws[ty + 2][tx + 2]) -
-                       (ws[ty + 2][tx] + ws[ty + 2][tx + 3])) * T(0.0625);
-        const T kyp = (T(9) * (ws[ty + 2][tx + 2] + ws[ty + 3][tx + 2]) -
-                       (ws[ty + 1][tx + 2] + ws[ty + 4][tx + 2])) * T(0.0625);
-        const T kym = (T(9) * (ws[ty + 1][tx + 2] + ws[ty + 2][tx + 2]) -
-                       (ws[ty][tx + 2] + ws[ty + 3][tx + 2])) * T(0.0625);
-        const T kzp = (T(9) * (wq2 + wq3) - (wq1 + wq4c)) * T(0.0625);
-        const T kzm = (T(9) * (wq1 + wq2) - (wq0 + wq3)) * T(0.0625);
-        const T lap = kxp * (pc - ps[ty + 1][tx + 2]) + kxm * (pc - ps[ty + 1][tx]) +
-                      kyp * (pc - ps[ty + 2][tx + 1]) + kym * (pc - ps[ty][tx + 1]) +
-                      kzp * (pc - pp) + kzm * (pc - pm);
-        const T sumK = kxp + kxm + kyp + kym + kzp + kzm;
-        const T qv = (dc - sumK * inv_h2) * pc + lap * inv_h2;
-        q[col + pl] = qv;
-        pnew[col + pl] = pc;
-        acc += (double)pc * (double)qv;
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) {
+            const int y = ty + e * kTY;
+            const T kxp = (T(9) * (ws[y + 2][tx + 2] + ws[y + 2][tx + 3]) -
+                           (ws[y + 2][tx + 1] + ws[y + 2][tx + 4])) * T(0.0625);
+            const T kxm = (T(9) * (ws[y + 2][tx + 1] + ws[y + 2][tx + 2]) -
+                           (ws[y + 2][tx] + ws[y + 2][tx + 3])) * T(0.0625);
+            const T kyp = (T(9) * (ws[y + 2][tx + 2] + ws[y + 3][tx + 2]) -
+                           (ws[y + 1][tx + 2] + ws[y + 4][tx + 2])) * T(0.0625);
+            const T kym = (T(9) * (ws[y + 1][tx + 2] + ws[y + 2][tx + 2]) -
+                           (ws[y][tx + 2] + ws[y + 3][tx + 2])) * T(0.0625);
+            const T kzp = (T(9) * (wq2[e] + wq3[e]) - (wq1[e] + wq4c[e])) * T(0.0625);
+            const T kzm = (T(9) * (wq1[e] + wq2[e]) - (wq0[e] + wq3[e])) * T(0.0625);
+            const T c0 = pc[e];
+            const T lap = kxp * (c0 - ps[y + 1][tx + 2]) + kxm * (c0 - ps[y + 1][tx]) +
+                          kyp * (c0 - ps[y + 2][tx + 1]) + kym * (c0 - ps[y][tx + 1]) +
+                          kzp * (c0 - pp[e]) + kzm * (c0 - pm[e]);
+            const T sumK = kxp + kxm + kyp + kym + kzp + kzm;
+            const T qv = (dc[e] - sumK * inv_h2) * c0 + lap * inv_h2;
+            q[col[e] + pl] = qv;
+            pnew[col[e] + pl] = c0;
+            acc += (double)c0 * (double)qv;
+        }
         lds_barrier();
-        wq0 = wq1;
-        wq1 = wq2;
-        wq2 = wq3;
-        wq3 = wq4c;
-        pm = pc;
-        pc = pp;
-        dc = dn;
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) {
+            wq0[e] = wq1[e];
+            wq1[e] = wq2[e];
+            wq2[e] = wq3[e];
+            wq3[e] = wq4c[e];
+            pm[e] = pc[e];
+            pc[e] = pp[e];
+            dc[e] = dn[e];
+        }
     }
     double v[1] = {acc};
     block_partials<1, 0u>(v, part_s);
@@ -1486,6 +1523,24 @@ Launch make_tiled_launch(int n, int batch) {
     return L;
 }
 
+Launch make_spmv_launch(int n, int batch) {
+    Launch L{};
+    constexpr int TY = kTY * kSpmvRows;
+    if (n < 128 || n % kTX != 0 || n % TY != 0) return L;   // nblocks = 0: not available
+    const int gx = n / kTX, gy = n / TY;
+    int nz = kTiledBlocks / (gx * gy);
+    nz = nz < 1 ? 1 : nz;
+    int cz = (n + nz - 1) / nz;
+    if (cz < 8) cz = 8;
+    nz = (n + cz - 1) / cz;
+    L.block = dim3(kTX, kTY, 1);
+    L.grid = dim3(gx, gy, nz * batch);
+    L.nblocks = L.grid.x * L.grid.y * L.grid.z;
+    L.cz = cz;
+    L.nz = nz;
+    return L;
+}
+
 static dim3 lin_grid(size_t count) {
     size_t b = (count + kBlock - 1) / kBlock;
     if (b > 65536) b = 65536;
@@ -1588,8 +1643,8 @@ void Ops<T>::pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Ph
         Phys pt = ph;
         pt.cz = TL.cz;
         pt.nz = TL.nz;
-        LAUNCH(k_pcg_spmv_tiled<T>, TL, s, pt, st, k, r, diag, w, pold, pnew, q, part_u, L.nblocks,
-               part_s, fresh, maxit);
+        LAUNCH((k_pcg_spmv_tiled<T, kSpmvRows>), TL, s, pt, st, k, r, diag, w, pold, pnew, q, part_u,
+               L.nblocks, part_s, fresh, maxit);
     } else {
         LAUNCH(k_pcg_spmv<T>, L, s, ph, st, k, r, diag, w, pold, pnew, q, part_u, part_s,
                L.nblocks, fresh, maxit);

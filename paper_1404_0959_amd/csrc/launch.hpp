@@ -34,6 +34,11 @@ Launch make_launch_shaped(int n, int batch, int bx, int cz);
 // is 0 when n is not a multiple of the tile or below 128.
 Launch make_tiled_launch(int n, int batch = 1);
 
+// Launch of the tiled CG first half: tiles of 64 x (8 kSpmvRows) cells, 64 x 8
+// threads each owning kSpmvRows rows; nblocks is 0 when not available.
+constexpr int kSpmvRows = 1;
+Launch make_spmv_launch(int n, int batch = 1);
+
 // Partial-sum slots in the workspace (columns of num_blocks doubles each).
 enum PartSlot {
     PS_CFL = 0,    // 1 column: Courant maxima
@@ -77,7 +82,7 @@ struct Ops {
                        const double* x64, const T* d, double* x64n, const double* b64,
                        const T* w, const T* diag, T* r32, double* part_u);
     static void zero(hipStream_t s, T* a, size_t count);
-    // TL: tiled launch (used when TL.nblocks > 0)
+    // TL: the tiled CG launch of make_spmv_launch (used when TL.nblocks > 0)
     static void pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                          DevState* st, int k, const T* r, const T* diag, const T* w,
                          const T* pold, T* pnew, T* q, const double* part_u, double* part_s,

@@ -143,6 +143,10 @@ __global__ void __launch_bounds__(256) k_conv16_rows(int n, int batch,
     v4s B[27];
 #pragma unroll
     for (int t = 0; t < 27; ++t) B[t] = wpk[t * 64 + lane];
+    // keep the weights in registers for the whole tile (the compiler would
+    // otherwise reload each one next to its products)
+#pragma unroll
+    for (int t = 0; t < 27; ++t) asm volatile("" : "+v"(B[t]));
     v4f acc[kRY][kRZ];
 #pragma unroll
     for (int oy = 0; oy < kRY; ++oy)
@@ -152,20 +156,33 @@ __global__ void __launch_bounds__(256) k_conv16_rows(int n, int batch,
     int xo[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) xo[q] = wrapn(iseg * 16 + m + q - 1, n);
-#pragma unroll
+    // the (kRY + 2) x (kRZ + 2) input rows in z-major order; each row's three
+    // x-shifted loads are issued two rows ahead of the products that use them
+    // (all loops fully unrolled: every row, tap and buffer index is a constant)
+    constexpr int kRW = kRY + 2, kRows = kRW * (kRZ + 2);
+    auto load_row = [&](int iz, int iy, v4s (&a)[3]) {
+        const size_t row = (size_t)n * ((size_t)wrapn(j0 - 1 + iy, n) + (size_t)n * wrapn(k0 - 1 + iz, n));
+#pragma clang loop unroll(full)
+        for (int q = 0; q < 3; ++q) a[q] = *reinterpret_cast<const v4s*>(inb + (row + xo[q]) * 16);
+    };
+    v4s abuf[3][3];
+    load_row(0, 0, abuf[0]);
+    load_row(0, 1, abuf[1]);
+#pragma clang loop unroll(full)
     for (int iz = 0; iz < kRZ + 2; ++iz) {
-        const int kk = wrapn(k0 - 1 + iz, n);
-#pragma unroll
-        for (int iy = 0; iy < kRY + 2; ++iy) {
-            const size_t row = (size_t)n * ((size_t)wrapn(j0 - 1 + iy, n) + (size_t)n * kk);
-#pragma unroll
+#pragma clang loop unroll(full)
+        for (int iy = 0; iy < kRW; ++iy) {
+            const int rrow = iz * kRW + iy;
+            if (rrow + 2 < kRows) load_row((rrow + 2) / kRW, (rrow + 2) % kRW, abuf[(rrow + 2) % 3]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma clang loop unroll(full)
             for (int q = 0; q < 3; ++q) {   // x shift dx = q - 1
-                const v4s a = *reinterpret_cast<const v4s*>(inb + (row + xo[q]) * 16);
-#pragma unroll
+                const v4s a = abuf[rrow % 3][q];
+#pragma clang loop unroll(full)
                 for (int oz = 0; oz < kRZ; ++oz) {
                     const int dz = iz - 1 - oz;
                     if (dz < -1 || dz > 1) continue;
-#pragma unroll
+#pragma clang loop unroll(full)
                     for (int oy = 0; oy < kRY; ++oy) {
                         const int dy = iy - 1 - oy;
                         if (dy < -1 || dy > 1) continue;
@@ -174,6 +191,7 @@ __global__ void __launch_bounds__(256) k_conv16_rows(int n, int batch,
                     }
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
     // lane holds D[4g + e][lane & 15] of each output row
@@ -194,6 +212,84 @@ __global__ void __launch_bounds__(256) k_conv16_rows(int n, int batch,
                     if (relu) v = v > 0.f ? v : 0.f;
                     out[P * 16 + nn] = f2bf(v);
                 }
+            }
+}
+
+// First layer (2 input channels, channel-last BF16 [cell][4] input) with input
+// reuse across output rows: a K-block covers one input-row offset (dy, dz),
+// lane group g holding the cell shifted by dx = g - 1 (group 3 idle), so each
+// input row is one 8-byte load per lane feeding every output row it touches:
+// 144 products per 36 loads for 16 cells x kRY x kRZ rows.  ReLU, BF16 out.
+__global__ void __launch_bounds__(256) k_conv4_rows(int n, int batch, const uint16_t* __restrict__ in,
+                                                    const v4s* __restrict__ wpk,
+                                                    uint16_t* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int segs = n / 16, nyb = n / kRY, nzb = n / kRZ;
+    const long nwaves = (long)batch * nzb * nyb * segs;
+    if (wave >= nwaves) return;  // whole wavefront; no block barrier below
+    const int iseg = (int)(wave % segs);
+    long rest = wave / segs;
+    const int j0 = (int)(rest % nyb) * kRY;
+    rest /= nyb;
+    const int k0 = (int)(rest % nzb) * kRZ;
+    const int b = (int)(rest / nzb);
+    const size_t N = (size_t)n * n * n;
+    const int m = lane & 15, g = lane >> 4;
+    v4s B[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) B[t] = wpk[t * 64 + lane];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) asm volatile("" : "+v"(B[t]));
+    v4f acc[kRY][kRZ];
+#pragma unroll
+    for (int oy = 0; oy < kRY; ++oy)
+#pragma unroll
+        for (int oz = 0; oz < kRZ; ++oz) acc[oy][oz] = v4f{0.f, 0.f, 0.f, 0.f};
+    const uint16_t* inb = in + (size_t)b * N * 4;
+    const int xo = wrapn(iseg * 16 + m + (g < 3 ? g - 1 : 0), n);   // group 3: weights are zero
+    constexpr int kRW = kRY + 2, kRows = kRW * (kRZ + 2);
+    auto load_row = [&](int iz, int iy) {
+        const size_t row = (size_t)n * ((size_t)wrapn(j0 - 1 + iy, n) + (size_t)n * wrapn(k0 - 1 + iz, n));
+        return *reinterpret_cast<const v4s*>(inb + (row + xo) * 4);
+    };
+    v4s abuf[3];
+    abuf[0] = load_row(0, 0);
+    abuf[1] = load_row(0, 1);
+#pragma clang loop unroll(full)
+    for (int iz = 0; iz < kRZ + 2; ++iz) {
+#pragma clang loop unroll(full)
+        for (int iy = 0; iy < kRW; ++iy) {
+            const int rrow = iz * kRW + iy;
+            if (rrow + 2 < kRows) abuf[(rrow + 2) % 3] = load_row((rrow + 2) / kRW, (rrow + 2) % kRW);
+            __builtin_amdgcn_sched_barrier(0);
+            const v4s a = abuf[rrow % 3];
+#pragma clang loop unroll(full)
+            for (int oz = 0; oz < kRZ; ++oz) {
+                const int dz = iz - 1 - oz;
+                if (dz < -1 || dz > 1) continue;
+#pragma clang loop unroll(full)
+                for (int oy = 0; oy < kRY; ++oy) {
+                    const int dy = iy - 1 - oy;
+                    if (dy < -1 || dy > 1) continue;
+                    acc[oy][oz] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, B[(dz + 1) * 3 + dy + 1],
+                                                                            acc[oy][oz], 0, 0, 0);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    const int nn = lane & 15;
+#pragma unroll
+    for (int oz = 0; oz < kRZ; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < kRY; ++oy)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const size_t cell = (size_t)(iseg * 16 + 4 * g + e) +
+                                    (size_t)n * ((size_t)(j0 + oy) + (size_t)n * (k0 + oz));
+                const float v = acc[oy][oz][e];
+                out[((size_t)b * N + cell) * 16 + nn] = f2bf(v > 0.f ? v : 0.f);
             }
 }
 
@@ -270,6 +366,26 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int nwaves, int c
     double s = 0.0;
     for (int w = 0; w < nwaves; ++w) s += (double)part[(size_t)w * NKB * 256 + idx];
     grad[((size_t)co * cin + ci) * 27 + tap] = (float)s;
+}
+
+// Pack the first layer (cin input channels, cout <= 16 outputs) for
+// k_conv4_rows: one K-block per input-row offset (dy, dz), t9 = (dz+1) 3 + (dy+1);
+// its K entry 4 g + c holds channel c of the cell dx = g - 1 along x (g < 3;
+// g = 3 and c >= cin are zero).
+__global__ void k_pack_rows4(const float* __restrict__ w, int cin, int cout, v4s* __restrict__ wpk) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 9 * 64) return;
+    const int kb = t / 64, lane = t % 64;
+    const int nn = lane & 15, g = lane >> 4;
+    const int tap = (kb / 3) * 9 + (kb % 3) * 3 + g;
+    v4s v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        float x = 0.f;
+        if (g < 3 && e < cin && nn < cout) x = w[((size_t)nn * cin + e) * 27 + tap];
+        v[e] = (short)f2bf(x);
+    }
+    wpk[t] = v;
 }
 
 // Pack one layer's FP32 weights [co][ci][27] into per-lane BF16 B operands.
@@ -355,7 +471,9 @@ size_t net_weight_offset(int layer) {
     return s;
 }
 
-size_t net_packed_bytes() { return (size_t)(7 + 27 + 27 + 27) * 64 * sizeof(v4s); }
+// Forward operands: layer 1 for k_conv (7 K-blocks), layers 2-4 (27 each), then
+// layer 1 again for k_conv4_rows (9 K-blocks).
+size_t net_packed_bytes() { return (size_t)(7 + 27 + 27 + 27 + 9) * 64 * sizeof(v4s); }
 
 void net_pack_forward(hipStream_t s, const float* w32, void* wpk) {
     v4s* p = reinterpret_cast<v4s*>(wpk);
@@ -367,6 +485,8 @@ void net_pack_forward(hipStream_t s, const float* w32, void* wpk) {
                            w32 + net_weight_offset(l), 16, kCh[l + 1], 0, p);
         p += 27 * 64;
     }
+    hipLaunchKernelGGL(k_pack_rows4, dim3((9 * 64 + 255) / 256), dim3(256), 0, s,
+                       w32 + net_weight_offset(0), 2, 16, p);
 }
 
 static dim3 conv_grid(int n, int batch) {
@@ -383,9 +503,8 @@ static dim3 conv_rows_grid(int n, int batch) {
 void net_forward(hipStream_t s, int n, int batch, const void* wpk, const uint16_t* x4,
                  uint16_t* a, uint16_t* b, float* y, float yscale) {
     const v4s* p = reinterpret_cast<const v4s*>(wpk);
-    const dim3 G = conv_grid(n, batch), GR = conv_rows_grid(n, batch), B(256);
-    hipLaunchKernelGGL((k_conv<4, false>), G, B, 0, s, n, batch, x4, p, (const uint16_t*)nullptr, 1, a,
-                       (float*)nullptr, 1.f);
+    const dim3 GR = conv_rows_grid(n, batch), B(256);
+    hipLaunchKernelGGL(k_conv4_rows, GR, B, 0, s, n, batch, x4, p + (7 + 27 + 27 + 27) * 64, a);
     p += 7 * 64;
     hipLaunchKernelGGL((k_conv16_rows<false>), GR, B, 0, s, n, batch, a, p, 1, b, (float*)nullptr,
                        1.f);

@@ -152,7 +152,8 @@ Layout make_layout(const pisoc_params* p, int batch) {
     Layout L{};
     const size_t N = (size_t)p->n * p->n * p->n * (size_t)batch;
     const size_t es = p->precision == PISOC_FP64 ? sizeof(double) : sizeof(float);
-    unsigned mb = std::max(make_launch(p->n, batch).nblocks, make_tiled_launch(p->n, batch).nblocks);
+    unsigned mb = std::max({make_launch(p->n, batch).nblocks, make_tiled_launch(p->n, batch).nblocks,
+                            make_spmv_launch(p->n, batch).nblocks});
     for (auto [bx, cz] : shape_candidates(p->n))
         mb = std::max(mb, make_launch_shaped(p->n, batch, bx, cz).nblocks);
     L.max_blocks = mb;
@@ -196,7 +197,8 @@ struct pisoc_ctx {
     Layout lay;
     Phys ph;
     Launch L;
-    Launch TL;      // tiled z-marching launch (nblocks = 0 when not available)
+    Launch TL;      // tiled z-marching launch of the field kernels (nblocks = 0: none)
+    Launch TS;      // tiled launch of the CG first half (nblocks = 0: none)
     DevState* st;
     DevState* hst = nullptr;  // pinned host copy (batch entries)
     double* partials;
@@ -320,13 +322,13 @@ pisoc_status run_pcg(pisoc_ctx* ctx, T* r, T* x, T* diag, T* w, T* pp0, T* pp1, 
     double* ps = ctx->part(PS_S);
     auto spmv = [&](int k) {
         timed(ctx, KC_PCG_SPMV, k == 0 ? 5.0 : 6.0, k, [&] {
-            O::pcg_spmv(ctx->L, ctx->TL, ctx->stream, ctx->ph, ctx->st, k, r, diag, w,
+            O::pcg_spmv(ctx->L, ctx->TS, ctx->stream, ctx->ph, ctx->st, k, r, diag, w,
                         pp[(k + 1) & 1], pp[k & 1], q, pu, ps, fresh ? 1 : 0, maxit);
         });
     };
     auto update = [&](int k) {
         timed(ctx, KC_PCG_UPDATE, 7.0, k, [&] {
-            O::pcg_update(ctx->L, ctx->TL, ctx->stream, ctx->ph, ctx->st, k, r, q, diag, x, pp[k & 1],
+            O::pcg_update(ctx->L, ctx->TS, ctx->stream, ctx->ph, ctx->st, k, r, q, diag, x, pp[k & 1],
                           ps, pu);
         });
     };
@@ -797,8 +799,9 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     ctx->lay = make_layout(prm, batch);
     const Layout& lay = ctx->lay;
     ctx->TL = make_tiled_launch(prm->n, batch);
-    // PISOC_UNTILED=1 selects the untiled CG kernel (kernel-comparison tests)
-    if (const char* e = std::getenv("PISOC_UNTILED"); e && e[0] == '1') ctx->TL = Launch{};
+    ctx->TS = make_spmv_launch(prm->n, batch);
+    // PISOC_UNTILED=1 selects the untiled kernels (kernel-comparison tests)
+    if (const char* e = std::getenv("PISOC_UNTILED"); e && e[0] == '1') ctx->TL = ctx->TS = Launch{};
     ctx->L = make_launch(prm->n, batch);
     ctx->ph = make_phys(prm, ctx->L, batch);
     ctx->st = reinterpret_cast<DevState*>(ctx->ws + lay.state);
@@ -1113,9 +1116,9 @@ void enqueue_probe(pisoc_ctx* ctx) {
     // two CG iterations that cannot stop early (tolerance 0, maxit above 2)
     set_tol(s, st, ctx->batch, 0.0);
     for (int k = 0; k < 2; ++k) {
-        O::pcg_spmv(L, ctx->TL, s, ph, st, k, S.r, S.dg, S.w, k ? S.pp0 : S.pp1, k ? S.pp1 : S.pp0,
+        O::pcg_spmv(L, ctx->TS, s, ph, st, k, S.r, S.dg, S.w, k ? S.pp0 : S.pp1, k ? S.pp1 : S.pp0,
                     S.q, ctx->part(PS_U), ctx->part(PS_S), 1, 1 << 20);
-        O::pcg_update(L, ctx->TL, s, ph, st, k, S.r, S.q, S.dg, S.x, k ? S.pp1 : S.pp0,
+        O::pcg_update(L, ctx->TS, s, ph, st, k, S.r, S.q, S.dg, S.x, k ? S.pp1 : S.pp0,
                       ctx->part(PS_S), ctx->part(PS_U));
     }
     if (ctx->prm.n_classes > 0) O::dust_sweep(L, s, ph, st, S.Ya, S.Yb, S.G, S.rj, S.rk);
@@ -1712,7 +1715,8 @@ const char* pisoc_ens_last_error(const pisoc_ens* e) { return e ? e->err.c_str()
 static Layout helm_layout(int32_t n) {
     Layout L{};
     const size_t N = (size_t)n * n * n;
-    L.max_blocks = std::max(make_launch(n, 1).nblocks, make_tiled_launch(n, 1).nblocks);
+    L.max_blocks = std::max({make_launch(n, 1).nblocks, make_tiled_launch(n, 1).nblocks,
+                             make_spmv_launch(n, 1).nblocks});
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     L.state = take(sizeof(DevState));
@@ -1770,6 +1774,7 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
     ctx.lay = lay;
     ctx.L = make_launch(n, 1);
     ctx.TL = make_tiled_launch(n, 1);
+    ctx.TS = make_spmv_launch(n, 1);
     ctx.ph = make_phys(&ctx.prm, ctx.L, 1);
     ctx.es = sizeof(double);
     ctx.st = reinterpret_cast<DevState*>(ctx.ws + lay.state);
