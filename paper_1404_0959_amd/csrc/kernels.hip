@@ -823,6 +823,154 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     block_partials<1, 0u>(v, part_s);
 }
 
+// Row form of the first half for n = 64 V: a block of kRowWaves wavefronts
+// owns as many consecutive full x-rows (wavefront v: row j0 + v; lane l:
+// cells x = V l .. V l + V - 1, one vector load per field) and marches along
+// z over cz planes.  A whole periodic row lives in one wavefront, so the
+// x neighbours come from the lane's own cells and one lane rotation and no
+// x halo is read.  y neighbours come from LDS rows (halo 2 for w, 1 for p)
+// loaded by wavefronts 0-5; z neighbours from per-lane register queues, the
+// lower z face coefficient carried over from the plane below.  Prefetches
+// past the chunk's last needed plane are clamped to planes already read.
+template <typename T, int V>
+__global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
+    Phys ph, DevState* st, int k, const T* __restrict__ r, const T* __restrict__ diag,
+    const T* __restrict__ w, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ q,
+    const double* part_u, unsigned nb_u, double* part_s, int fresh, int maxit) {
+    using VT = T __attribute__((ext_vector_type(V)));
+    static_assert(kRowWaves >= 6, "wavefronts 0-5 load the y halo rows");
+    MEMBER(ph)
+    if (k >= (st + mem_)->pcg.it_stop) return;
+    double t[3];
+    reduce_member<3, 0u>(part_u, nb_u, ph.batch, mem_, t);
+    const double rz = t[0], rr = t[1];
+    const bool newb = fresh && k == 0;
+    const double bb = newb ? t[2] : (st + mem_)->pcg.bb;
+    const double tol2 = (st + mem_)->pcg.tol2;
+    const bool conv = rr <= tol2 * bb;
+    const bool stop = conv || k >= maxit;
+    if (MEMBER_FIRST()) {
+        PcgState& g = (st + mem_)->pcg;
+        g.rr = rr;
+        g.iters = k;
+        g.rzh[k & 1] = rz;
+        if (newb) g.bb = bb;
+        if (stop) {
+            g.it_stop = k;
+            g.converged = conv ? 1 : 0;
+        }
+    }
+    if (stop) return;
+    const T beta = k == 0 ? T(0) : (T)(rz / (st + mem_)->pcg.rzh[(k - 1) & 1]);
+    const bool first = k == 0;
+    const T inv_h2 = (T)ph.inv_h2;
+    const int n = ph.n, cz = ph.cz;   // n == 64 V
+    constexpr int TY = kRowWaves;
+    const int lane = threadIdx.x, wv = threadIdx.y;
+    const int j0 = bp_.y * TY;
+    const int k0 = bz_ * cz;
+    const int k1 = k0 + cz < n ? k0 + cz : n;
+    const size_t nn = (size_t)n * n;
+    __shared__ VT wl[TY + 4][64];   // w of rows j0 - 2 .. j0 + TY + 1
+    __shared__ VT pl[TY + 2][64];   // p of rows j0 - 1 .. j0 + TY
+    auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
+    auto ld = [](const T* f, size_t o) { return *reinterpret_cast<const VT*>(f + o); };
+    auto sel = [&](VT v) { return first ? VT(T(0)) : v; };
+    const size_t col = base_ + (size_t)n * (j0 + wv) + (size_t)V * lane;
+    // this wavefront's y halo row: w rows j0-2, j0-1, j0+TY, j0+TY+1 (waves
+    // 0-3), p rows j0-1, j0+TY (waves 4-5, from r, diag and p_old); waves 6..
+    // read their own row so that every load is unconditional
+    const int hrow = wv < 2 ? j0 - 2 + wv : wv < 4 ? j0 + TY - 2 + wv
+                   : wv == 4 ? j0 - 1 : wv == 5 ? j0 + TY : j0 + wv;
+    const size_t hcol = base_ + (size_t)n * wr(hrow) + (size_t)V * lane;
+    const T* hsrc = wv < 4 ? w : r;
+    auto plane = [&](int kk) { return nn * (size_t)wr(kk); };
+    const VT wmm = ld(w, col + plane(k0 - 2));
+    VT wm1 = ld(w, col + plane(k0 - 1)), w0 = ld(w, col + plane(k0)), wp1 = ld(w, col + plane(k0 + 1));
+    VT wp2n = ld(w, col + plane(k0 + 2));
+    VT pm = ld(r, col + plane(k0 - 1)) / ld(diag, col + plane(k0 - 1)) + beta * sel(ld(pold, col + plane(k0 - 1)));
+    VT pc = ld(r, col + plane(k0)) / ld(diag, col + plane(k0)) + beta * sel(ld(pold, col + plane(k0)));
+    VT dc = ld(diag, col + plane(k0));
+    VT rnx = ld(r, col + plane(k0 + 1)), dnx = ld(diag, col + plane(k0 + 1)), onx = ld(pold, col + plane(k0 + 1));
+    VT h1 = ld(hsrc, hcol + plane(k0)), h2 = ld(diag, hcol + plane(k0)), h3 = ld(pold, hcol + plane(k0));
+    VT kzm = (T(9) * (wm1 + w0) - (wmm + wp1)) * T(0.0625);
+    auto from_left = [&](T v) { return __shfl(v, (lane + 63) & 63, 64); };
+    auto from_right = [&](T v) { return __shfl(v, (lane + 1) & 63, 64); };
+    double acc = 0.0;
+    for (int kk = k0; kk < k1; ++kk) {
+        const VT wp2 = wp2n;
+        const VT pp = rnx / dnx + beta * sel(onx);
+        const VT dn = dnx;
+        const VT hw = h1, hp = h1 / h2 + beta * sel(h3);
+        {
+            const int kw = kk + 3 < k1 + 1 ? kk + 3 : k1 + 1;   // last w plane needed: k1 + 1
+            const int kp = kk + 2 < k1 ? kk + 2 : k1;           // last p plane needed: k1
+            const int kh = kk + 1 < k1 - 1 ? kk + 1 : k1 - 1;   // last halo plane: k1 - 1
+            wp2n = ld(w, col + plane(kw));
+            rnx = ld(r, col + plane(kp));
+            dnx = ld(diag, col + plane(kp));
+            onx = ld(pold, col + plane(kp));
+            h1 = ld(hsrc, hcol + plane(kh));
+            h2 = ld(diag, hcol + plane(kh));
+            h3 = ld(pold, hcol + plane(kh));
+        }
+        wl[wv + 2][lane] = w0;
+        pl[wv + 1][lane] = pc;
+        if (wv < 2) wl[wv][lane] = hw;
+        else if (wv < 4) wl[TY + wv][lane] = hw;
+        else if (wv == 4) pl[0][lane] = hp;
+        else if (wv == 5) pl[TY + 1][lane] = hp;
+        lds_barrier();
+        const VT ym2 = wl[wv][lane], ym1 = wl[wv + 1][lane], yp1 = wl[wv + 3][lane], yp2 = wl[wv + 4][lane];
+        const VT pym = pl[wv][lane], pyp = pl[wv + 2][lane];
+        lds_barrier();
+        // w at x - 2 .. x + V + 1 and p at x - 1 .. x + V of this lane's cells
+        T wx[V + 4], px[V + 2];
+        wx[0] = from_left(w0[V - 2]);
+        wx[1] = from_left(w0[V - 1]);
+        wx[V + 2] = from_right(w0[0]);
+        wx[V + 3] = from_right(w0[1]);
+        px[0] = from_left(pc[V - 1]);
+        px[V + 1] = from_right(pc[0]);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            wx[i + 2] = w0[i];
+            px[i + 1] = pc[i];
+        }
+        T kf[V + 1];   // x face coefficients, face f between cells f - 1 and f
+#pragma unroll
+        for (int f = 0; f <= V; ++f)
+            kf[f] = (T(9) * (wx[f + 1] + wx[f + 2]) - (wx[f] + wx[f + 3])) * T(0.0625);
+        const VT kzp = (T(9) * (w0 + wp1) - (wm1 + wp2)) * T(0.0625);
+        VT qo;
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const T kxp = kf[i + 1], kxm = kf[i];
+            const T kyp = (T(9) * (w0[i] + yp1[i]) - (ym1[i] + yp2[i])) * T(0.0625);
+            const T kym = (T(9) * (ym1[i] + w0[i]) - (ym2[i] + yp1[i])) * T(0.0625);
+            const T c0 = pc[i];
+            const T lap = kxp * (c0 - px[i + 2]) + kxm * (c0 - px[i]) + kyp * (c0 - pyp[i]) +
+                          kym * (c0 - pym[i]) + kzp[i] * (c0 - pp[i]) + kzm[i] * (c0 - pm[i]);
+            const T sumK = kxp + kxm + kyp + kym + kzp[i] + kzm[i];
+            const T qv = (dc[i] - sumK * inv_h2) * c0 + lap * inv_h2;
+            qo[i] = qv;
+            acc += (double)c0 * (double)qv;
+        }
+        const size_t pl0 = nn * (size_t)kk;
+        *reinterpret_cast<VT*>(q + col + pl0) = qo;
+        *reinterpret_cast<VT*>(pnew + col + pl0) = pc;
+        wm1 = w0;
+        w0 = wp1;
+        wp1 = wp2;
+        kzm = kzp;
+        pm = pc;
+        pc = pp;
+        dc = dn;
+    }
+    double v[1] = {acc};
+    block_partials<1, 0u>(v, part_s);
+}
+
 // Iteration k, second half: alpha_k = r_k.z_k / p_k.q from the previous
 // kernel's partials, x += alpha p, r -= alpha q, and partial sums of
 // r.(r/diag) and r.r for the next first half.
@@ -1525,6 +1673,20 @@ Launch make_tiled_launch(int n, int batch) {
 
 Launch make_spmv_launch(int n, int batch) {
     Launch L{};
+    if (n == 64 * kRowCells) {   // full-row form
+        const int gy = n / kRowWaves;
+        int nz = kRowBlocks / gy;
+        nz = nz < 1 ? 1 : nz;
+        const int cz = (n + nz - 1) / nz;
+        nz = (n + cz - 1) / cz;
+        L.block = dim3(64, kRowWaves, 1);
+        L.grid = dim3(1, gy, nz * batch);
+        L.nblocks = L.grid.x * L.grid.y * L.grid.z;
+        L.cz = cz;
+        L.nz = nz;
+        L.v = kRowCells;
+        return L;
+    }
     constexpr int TY = kTY * kSpmvRows;
     if (n < 128 || n % kTX != 0 || n % TY != 0) return L;   // nblocks = 0: not available
     const int gx = n / kTX, gy = n / TY;
@@ -1639,7 +1801,13 @@ template <typename T>
 void Ops<T>::pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                       DevState* st, int k, const T* r, const T* diag, const T* w, const T* pold,
                       T* pnew, T* q, const double* part_u, double* part_s, int fresh, int maxit) {
-    if (TL.nblocks) {
+    if (TL.nblocks && TL.v == kRowCells) {
+        Phys pt = ph;
+        pt.cz = TL.cz;
+        pt.nz = TL.nz;
+        LAUNCH((k_pcg_spmv_rows<T, kRowCells>), TL, s, pt, st, k, r, diag, w, pold, pnew, q, part_u,
+               L.nblocks, part_s, fresh, maxit);
+    } else if (TL.nblocks) {
         Phys pt = ph;
         pt.cz = TL.cz;
         pt.nz = TL.nz;

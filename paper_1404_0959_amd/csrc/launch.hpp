@@ -16,6 +16,7 @@ struct Launch {
     unsigned nblocks;   // all members
     int cz;             // cells per thread along z
     int nz;             // blocks per member along z
+    int v = 0;          // CG first half: cells per lane along x of the full-row form (0: tiles)
 };
 
 constexpr int kTargetBlocks = 2048;
@@ -34,9 +35,13 @@ Launch make_launch_shaped(int n, int batch, int bx, int cz);
 // is 0 when n is not a multiple of the tile or below 128.
 Launch make_tiled_launch(int n, int batch = 1);
 
-// Launch of the tiled CG first half: tiles of 64 x (8 kSpmvRows) cells, 64 x 8
-// threads each owning kSpmvRows rows; nblocks is 0 when not available.
+// Launch of the CG first half.  For n = 64 kRowCells: the full-row form, blocks
+// of kRowWaves wavefronts each owning one x-row (kRowCells cells per lane),
+// about kRowBlocks blocks per member (v = kRowCells).  Otherwise tiles of
+// 64 x (8 kSpmvRows) cells, 64 x 8 threads each owning kSpmvRows rows
+// (v = 0); nblocks is 0 when neither is available.
 constexpr int kSpmvRows = 1;
+constexpr int kRowCells = 4, kRowWaves = 8, kRowBlocks = 256;
 Launch make_spmv_launch(int n, int batch = 1);
 
 // Partial-sum slots in the workspace (columns of num_blocks doubles each).

@@ -117,16 +117,17 @@ __global__ void __launch_bounds__(256) k_conv(int n, int batch, const uint16_t* 
 // each input row, taken at the three x shifts, is loaded once (8 bytes per
 // lane: 4 channels of one cell) and fed to the matrix cores for every output
 // row and tap it contributes to -- 432 products per 108 loads, where the
-// row-at-a-time kernel issues one load per product.  Output as k_conv
-// (ReLU to BF16, or with FINAL channel 0 in FP32 times yscale).
+// row-at-a-time kernel issues one load per product.  Output: 16 BF16
+// channels per cell (ReLU when relu is set).
 constexpr int kRY = 4, kRZ = 4;
+// input rows whose loads are in flight ahead of the products that use them
+// (at occupancy 2 the registers allow it; 8 measured fastest of 2, 4, 6, 8)
+constexpr int kAhead = 8;
 
-template <bool FINAL>
 __global__ void __launch_bounds__(256) k_conv16_rows(int n, int batch,
                                                      const uint16_t* __restrict__ in,
                                                      const v4s* __restrict__ wpk, int relu,
-                                                     uint16_t* __restrict__ out,
-                                                     float* __restrict__ yout, float yscale) {
+                                                     uint16_t* __restrict__ out) {
     const int lane = threadIdx.x & 63;
     const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int segs = n / 16, nyb = n / kRY, nzb = n / kRZ;
@@ -157,27 +158,29 @@ __global__ void __launch_bounds__(256) k_conv16_rows(int n, int batch,
 #pragma unroll
     for (int q = 0; q < 3; ++q) xo[q] = wrapn(iseg * 16 + m + q - 1, n);
     // the (kRY + 2) x (kRZ + 2) input rows in z-major order; each row's three
-    // x-shifted loads are issued two rows ahead of the products that use them
-    // (all loops fully unrolled: every row, tap and buffer index is a constant)
+    // x-shifted loads are issued kAhead rows ahead of the products that use
+    // them (all loops fully unrolled: every row, tap and buffer index is a
+    // constant)
     constexpr int kRW = kRY + 2, kRows = kRW * (kRZ + 2);
-    auto load_row = [&](int iz, int iy, v4s (&a)[3]) {
+    auto load_row = [&](int rrow, v4s (&a)[3]) {
+        const int iz = rrow / kRW, iy = rrow % kRW;
         const size_t row = (size_t)n * ((size_t)wrapn(j0 - 1 + iy, n) + (size_t)n * wrapn(k0 - 1 + iz, n));
 #pragma clang loop unroll(full)
         for (int q = 0; q < 3; ++q) a[q] = *reinterpret_cast<const v4s*>(inb + (row + xo[q]) * 16);
     };
-    v4s abuf[3][3];
-    load_row(0, 0, abuf[0]);
-    load_row(0, 1, abuf[1]);
+    v4s abuf[kAhead + 1][3];
+#pragma clang loop unroll(full)
+    for (int r = 0; r < kAhead; ++r) load_row(r, abuf[r]);
 #pragma clang loop unroll(full)
     for (int iz = 0; iz < kRZ + 2; ++iz) {
 #pragma clang loop unroll(full)
         for (int iy = 0; iy < kRW; ++iy) {
             const int rrow = iz * kRW + iy;
-            if (rrow + 2 < kRows) load_row((rrow + 2) / kRW, (rrow + 2) % kRW, abuf[(rrow + 2) % 3]);
+            if (rrow + kAhead < kRows) load_row(rrow + kAhead, abuf[(rrow + kAhead) % (kAhead + 1)]);
             __builtin_amdgcn_sched_barrier(0);
 #pragma clang loop unroll(full)
             for (int q = 0; q < 3; ++q) {   // x shift dx = q - 1
-                const v4s a = abuf[rrow % 3][q];
+                const v4s a = abuf[rrow % (kAhead + 1)][q];
 #pragma clang loop unroll(full)
                 for (int oz = 0; oz < kRZ; ++oz) {
                     const int dz = iz - 1 - oz;
@@ -204,15 +207,86 @@ __global__ void __launch_bounds__(256) k_conv16_rows(int n, int batch,
             for (int e = 0; e < 4; ++e) {
                 const size_t cell = (size_t)(iseg * 16 + 4 * g + e) +
                                     (size_t)n * ((size_t)(j0 + oy) + (size_t)n * (k0 + oz));
-                const size_t P = (size_t)b * N + cell;
                 float v = acc[oy][oz][e];
-                if (FINAL) {
-                    if (nn == 0) yout[P] = v * yscale;
-                } else {
-                    if (relu) v = v > 0.f ? v : 0.f;
-                    out[P * 16 + nn] = f2bf(v);
-                }
+                if (relu) v = v > 0.f ? v : 0.f;
+                out[((size_t)b * N + cell) * 16 + nn] = f2bf(v);
             }
+}
+
+// Last layer (16 inputs, 1 output): the kRY x kRZ = 16 output rows of the block
+// are the 16 matrix columns, so one product per input row and x shift covers
+// them all (108 products per tile instead of 432 with 15 of 16 columns idle).
+// For input row (iy, iz) at x shift dx = q - 1 the B operand is
+// B[ci][n] = W[ci][tap(dx, iy - 1 - oy, iz - 1 - oz)] for output row
+// n = oy + kRY oz, zero where the offset is out of reach.  The block keeps W in
+// LDS on a zero-padded (dz, dy) grid of [-4, 4]^2, so every lane reads its B
+// operand at its own base plus a compile-time offset.  A is the input row as in
+// k_conv16_rows.  y = yscale * output, FP32.
+constexpr int kPadW = 9;   // dy, dz in [-4, 4]
+__global__ void __launch_bounds__(256) k_conv16_final_rows(int n, int batch,
+                                                           const uint16_t* __restrict__ in,
+                                                           const v4s* __restrict__ wfin,
+                                                           float* __restrict__ yout, float yscale) {
+    static_assert(kRY * kRZ == 16, "output rows fill the 16 matrix columns");
+    static_assert(kRY <= 4 && kRZ <= 4, "padded grid covers every row offset");
+    // wl[((dz + 4) kPadW + dy + 4) 3 + q][g]: channels 4g..4g+3 of tap (q - 1, dy, dz)
+    __shared__ v4s wl[kPadW * kPadW * 3 * 4];
+    for (int i = threadIdx.x; i < kPadW * kPadW * 3 * 4; i += blockDim.x) {
+        const int g = i % 4, e = i / 4, q = e % 3, dy = (e / 3) % kPadW - 4, dz = e / (3 * kPadW) - 4;
+        const bool reach = dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+        wl[i] = reach ? wfin[((dz + 1) * 9 + (dy + 1) * 3 + q) * 4 + g] : v4s{0, 0, 0, 0};
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int segs = n / 16, nyb = n / kRY, nzb = n / kRZ;
+    const long nwaves = (long)batch * nzb * nyb * segs;
+    if (wave >= nwaves) return;  // whole wavefront; no block barrier below
+    const int iseg = (int)(wave % segs);
+    long rest = wave / segs;
+    const int j0 = (int)(rest % nyb) * kRY;
+    rest /= nyb;
+    const int k0 = (int)(rest % nzb) * kRZ;
+    const int b = (int)(rest / nzb);
+    const size_t N = (size_t)n * n * n;
+    const int m = lane & 15, g = lane >> 4;
+    const int nn = lane & 15, oy = nn % kRY, oz = nn / kRY;
+    // entry of (iy, iz, q) for this lane: wbase + ((iz kPadW + iy) 3 + q) 4
+    const v4s* wbase = wl + (((3 - oz) * kPadW + (3 - oy)) * 3) * 4 + g;
+    const uint16_t* inb = in + (size_t)b * N * 16 + 4 * g;
+    int xo[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) xo[q] = wrapn(iseg * 16 + m + q - 1, n);
+    constexpr int kRW = kRY + 2, kRows = kRW * (kRZ + 2);
+    auto load_row = [&](int rrow, v4s (&a)[3]) {
+        const int iz = rrow / kRW, iy = rrow % kRW;
+        const size_t row = (size_t)n * ((size_t)wrapn(j0 - 1 + iy, n) + (size_t)n * wrapn(k0 - 1 + iz, n));
+#pragma clang loop unroll(full)
+        for (int q = 0; q < 3; ++q) a[q] = *reinterpret_cast<const v4s*>(inb + (row + xo[q]) * 16);
+    };
+    v4s abuf[kAhead + 1][3];
+#pragma clang loop unroll(full)
+    for (int r = 0; r < kAhead; ++r) load_row(r, abuf[r]);
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma clang loop unroll(full)
+    for (int rrow = 0; rrow < kRows; ++rrow) {
+        if (rrow + kAhead < kRows) load_row(rrow + kAhead, abuf[(rrow + kAhead) % (kAhead + 1)]);
+        __builtin_amdgcn_sched_barrier(0);
+        const int iz = rrow / kRW, iy = rrow % kRW;
+#pragma clang loop unroll(full)
+        for (int q = 0; q < 3; ++q)
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(abuf[rrow % (kAhead + 1)][q],
+                                                            wbase[((iz * kPadW + iy) * 3 + q) * 4],
+                                                            acc, 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // lane holds D[4g + e][lane & 15]: cell 4g + e of output row lane & 15
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const size_t cell = (size_t)(iseg * 16 + 4 * g + e) +
+                            (size_t)n * ((size_t)(j0 + oy) + (size_t)n * (k0 + oz));
+        yout[(size_t)b * N + cell] = acc[e] * yscale;
+    }
 }
 
 // First layer (2 input channels, channel-last BF16 [cell][4] input) with input
@@ -253,17 +327,18 @@ __global__ void __launch_bounds__(256) k_conv4_rows(int n, int batch, const uint
         const size_t row = (size_t)n * ((size_t)wrapn(j0 - 1 + iy, n) + (size_t)n * wrapn(k0 - 1 + iz, n));
         return *reinterpret_cast<const v4s*>(inb + (row + xo) * 4);
     };
-    v4s abuf[3];
-    abuf[0] = load_row(0, 0);
-    abuf[1] = load_row(0, 1);
+    v4s abuf[kAhead + 1];
+#pragma clang loop unroll(full)
+    for (int r = 0; r < kAhead; ++r) abuf[r] = load_row(r / kRW, r % kRW);
 #pragma clang loop unroll(full)
     for (int iz = 0; iz < kRZ + 2; ++iz) {
 #pragma clang loop unroll(full)
         for (int iy = 0; iy < kRW; ++iy) {
             const int rrow = iz * kRW + iy;
-            if (rrow + 2 < kRows) abuf[(rrow + 2) % 3] = load_row((rrow + 2) / kRW, (rrow + 2) % kRW);
+            if (rrow + kAhead < kRows)
+                abuf[(rrow + kAhead) % (kAhead + 1)] = load_row((rrow + kAhead) / kRW, (rrow + kAhead) % kRW);
             __builtin_amdgcn_sched_barrier(0);
-            const v4s a = abuf[rrow % 3];
+            const v4s a = abuf[rrow % (kAhead + 1)];
 #pragma clang loop unroll(full)
             for (int oz = 0; oz < kRZ; ++oz) {
                 const int dz = iz - 1 - oz;
@@ -388,6 +463,18 @@ __global__ void k_pack_rows4(const float* __restrict__ w, int cin, int cout, v4s
     wpk[t] = v;
 }
 
+// Pack the last layer (16 inputs, 1 output) for k_conv16_final_rows:
+// wfin[tap * 4 + g] = BF16 W[0][4g + e][tap], e = 0..3.
+__global__ void k_pack_final(const float* __restrict__ w, v4s* __restrict__ wfin) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 27 * 4) return;
+    const int tap = t / 4, g = t % 4;
+    v4s v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (short)f2bf(w[(size_t)(4 * g + e) * 27 + tap]);
+    wfin[t] = v;
+}
+
 // Pack one layer's FP32 weights [co][ci][27] into per-lane BF16 B operands.
 // Forward: out channel n = co, K entry (tap, ci).  Data gradient (tflip): out
 // channel n = ci, K entry (tap', co) with weight W[co][ci][26 - tap'].
@@ -471,9 +558,10 @@ size_t net_weight_offset(int layer) {
     return s;
 }
 
-// Forward operands: layer 1 for k_conv (7 K-blocks), layers 2-4 (27 each), then
-// layer 1 again for k_conv4_rows (9 K-blocks).
-size_t net_packed_bytes() { return (size_t)(7 + 27 + 27 + 27 + 9) * 64 * sizeof(v4s); }
+// Forward operands: layer 1 for k_conv (7 K-blocks), layers 2-4 (27 each),
+// layer 1 again for k_conv4_rows (9 K-blocks), then layer 4 for
+// k_conv16_final_rows (27 taps x 4 channel groups).
+size_t net_packed_bytes() { return ((size_t)(7 + 27 + 27 + 27 + 9) * 64 + 27 * 4) * sizeof(v4s); }
 
 void net_pack_forward(hipStream_t s, const float* w32, void* wpk) {
     v4s* p = reinterpret_cast<v4s*>(wpk);
@@ -487,6 +575,8 @@ void net_pack_forward(hipStream_t s, const float* w32, void* wpk) {
     }
     hipLaunchKernelGGL(k_pack_rows4, dim3((9 * 64 + 255) / 256), dim3(256), 0, s,
                        w32 + net_weight_offset(0), 2, 16, p);
+    p += 9 * 64;
+    hipLaunchKernelGGL(k_pack_final, dim3(1), dim3(128), 0, s, w32 + net_weight_offset(3), p);
 }
 
 static dim3 conv_grid(int n, int batch) {
@@ -506,14 +596,12 @@ void net_forward(hipStream_t s, int n, int batch, const void* wpk, const uint16_
     const dim3 GR = conv_rows_grid(n, batch), B(256);
     hipLaunchKernelGGL(k_conv4_rows, GR, B, 0, s, n, batch, x4, p + (7 + 27 + 27 + 27) * 64, a);
     p += 7 * 64;
-    hipLaunchKernelGGL((k_conv16_rows<false>), GR, B, 0, s, n, batch, a, p, 1, b, (float*)nullptr,
-                       1.f);
+    hipLaunchKernelGGL(k_conv16_rows, GR, B, 0, s, n, batch, a, p, 1, b);
     p += 27 * 64;
-    hipLaunchKernelGGL((k_conv16_rows<false>), GR, B, 0, s, n, batch, b, p, 1, a, (float*)nullptr,
-                       1.f);
+    hipLaunchKernelGGL(k_conv16_rows, GR, B, 0, s, n, batch, b, p, 1, a);
     p += 27 * 64;
-    hipLaunchKernelGGL((k_conv16_rows<true>), GR, B, 0, s, n, batch, a, p, 0, (uint16_t*)nullptr, y,
-                       yscale);
+    hipLaunchKernelGGL(k_conv16_final_rows, GR, B, 0, s, n, batch, a,
+                       reinterpret_cast<const v4s*>(wpk) + (7 + 27 + 27 + 27 + 9) * 64, y, yscale);
 }
 
 // ---- training workspace ----

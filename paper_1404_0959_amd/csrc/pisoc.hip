@@ -1775,6 +1775,8 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
     ctx.L = make_launch(n, 1);
     ctx.TL = make_tiled_launch(n, 1);
     ctx.TS = make_spmv_launch(n, 1);
+    // the full-row CG kernel reads w with vector loads of kRowCells doubles
+    if (reinterpret_cast<uintptr_t>(d_w) % (kRowCells * sizeof(double)) != 0 && ctx.TS.v) ctx.TS = Launch{};
     ctx.ph = make_phys(&ctx.prm, ctx.L, 1);
     ctx.es = sizeof(double);
     ctx.st = reinterpret_cast<DevState*>(ctx.ws + lay.state);

@@ -67,6 +67,21 @@ def test_fp32_vs_oracle(P, ora, n, steps):
     check_fields(P, ora, s, o, FIELD_TOL)
 
 
+def test_fp32_bench_workload_vs_oracle(P, ora):
+    """One step of the 256^3 benchmark workload in the benchmark's FP32 settings
+    (inner tolerance 1e-6): the full-row CG kernel in FP32."""
+    case = make_hit_case(256, 0, mach=0.2, stokes=(0.2,))
+    tol = 1e-6
+    o = ora.Oracle.from_case(case, p_tol=tol)
+    s = P.Solver.from_case(case, p_tol=tol, precision=P.FP32_REFINED, inner_tol=1e-6)
+    o.step(1)
+    st, info = s.step(1)
+    assert st == 0
+    for i in info:
+        assert all(r <= tol for r in i["pcg_relres"]), i
+    check_fields(P, ora, s, o, FIELD_TOL)
+
+
 def test_fp32_mass_budget(P):
     """FP64 reductions of FP32 fields: the face fluxes telescope, so total gas
     and dust mass only drift by the FP32 rounding of the per-cell updates, an
