@@ -182,8 +182,8 @@ def ensemble_run(P, torch, args, weights):
 KERNEL_SOURCES = ("kernels.hip", "device.hpp", "launch.hpp", "net.hip")
 # dominant kernel class -> the 256^3 kernel whose HBM bytes the committed
 # counter summary holds
-TRAFFIC_NAME = {("k_pcg_spmv", "f32+f64"): "k_pcg_spmv_tiled<float>",
-                ("k_pcg_spmv", "f64"): "k_pcg_spmv_tiled<double>",
+TRAFFIC_NAME = {("k_pcg_spmv", "f32+f64"): "k_pcg_spmv_rows<float, 4>",
+                ("k_pcg_spmv", "f64"): "k_pcg_spmv_rows<double, 4>",
                 ("k_pcg_update", "f32+f64"): "k_pcg_update<float>",
                 ("k_pcg_update", "f64"): "k_pcg_update<double>"}
 
