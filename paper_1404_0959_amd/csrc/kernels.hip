@@ -440,16 +440,17 @@ __global__ void __launch_bounds__(kTX * kTY) k_mom_sweep_tiled(
 //   b = -[(rho_k - rho^n)/dt + div(phiH - K A snGrad p0)],  K = I4(w),
 //   diag(M) = psi/dt + sum K / h^2,  psi = rho/(gamma p) = 1/(gamma C rho^(gamma-1)).
 // The continuity defect is evaluated in FP64 arithmetic whatever T is (it is
-// a small difference of large fluxes).  Starts CG from x = 0: r = b and
-// partial sums of b.(b/diag), b.b, b.b.  With b64 non-null (FP32 storage) the
-// FP64 defect is also kept, and the FP64 solution accumulator x64 zeroed.
+// a small difference of large fluxes).  CG starts from x = 0: r = b and
+// partial sums of b.(b/diag), b.b, b.b; x itself is not written (the first
+// x update writes rather than adds).  With b64 non-null (FP32 storage) the
+// FP64 defect is also kept (the first refinement takes the FP64 accumulator
+// as zero).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_corr_rhs(
     Phys ph, DevState* st, const T* __restrict__ rn, const T* __restrict__ rk,
     const T* __restrict__ w, const T* __restrict__ hbya, const T* __restrict__ p0,
-    T* __restrict__ phiH, T* __restrict__ rvec, T* __restrict__ x, T* __restrict__ diag,
-    double* part_u, double* snap_b, double* snap_diag, double* snap_p0, double* b64,
-    double* x64) {
+    T* __restrict__ phiH, T* __restrict__ rvec, T* __restrict__ diag, double* part_u,
+    double* snap_b, double* snap_diag, double* snap_p0, double* b64) {
     MEMBER(ph)
     const size_t N = ncell(ph);
     const double dt = (st + mem_)->dt;
@@ -488,16 +489,12 @@ __global__ void __launch_bounds__(kBlock) k_corr_rhs(
     const T dgT = (T)(psidt + sumK * inv_h2);
     const T bT = (T)b;
     rvec[P] = bT;
-    x[P] = T(0);
     diag[P] = dgT;
     const double bd = (double)bT;
     v[0] += bd * (bd / (double)dgT);
     v[1] += b64 ? b * b : bd * bd;
     v[2] += b64 ? b * b : bd * bd;
-    if (b64) {
-        b64[P] = b;
-        x64[P] = 0.0;
-    }
+    if (b64) b64[P] = b;
     if (snap_b) {
         snap_b[P] = b;
         snap_diag[P] = (double)dgT;
@@ -516,8 +513,10 @@ __global__ void __launch_bounds__(kBlock) k_corr_rhs(
 // correction, x64_new = x64 + d, evaluate r64 = b64 - M x64_new in FP64
 // arithmetic (coefficients K = I4(w) and diag from their FP32 storage), and
 // set up the next inner solve's right-hand side float(r64) with partial sums
-// r.(r/diag), ||r64||^2, ||r64||^2 (the inner correction d is zeroed after).
-template <typename T>
+// r.(r/diag), ||r64||^2, ||r64||^2.  FROM_ZERO: x64 is zero (the first round
+// of a solve started from zero) and is not read.  The next inner solve
+// starts from d = 0 without d being written.
+template <typename T, bool FROM_ZERO>
 __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
                                                    const double* __restrict__ x64,
                                                    const T* __restrict__ d, double* __restrict__ x64n,
@@ -529,9 +528,9 @@ __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
     double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
     T wv[13], dv[7];
-    double xv[7];
+    double xv[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     gather13(w, c, wv);
-    gather7(x64, c, xv);
+    if (!FROM_ZERO) gather7(x64, c, xv);
     gather7(d, c, dv);
     const double bP = b64[P];
     const T dgP = diag[P];
@@ -577,15 +576,22 @@ __global__ void k_zero(T* __restrict__ a, size_t count) {
 // decision).  Otherwise: direction p_k = z_k + beta_{k-1} p_{k-1} with
 // z = r / diag recomputed on the stencil (not stored), q = M p_k with the face
 // coefficients K = I4(w) formed on the fly, and partial sums of p_k.q.
-template <typename T>
+// XUPD (k >= 1): the previous iteration's x += alpha_{k-1} p_{k-1} is applied
+// here, where p_{k-1} is read anyway, also when the solve stops; with xzero
+// (the solve started from x = 0, not written) it writes x at k = 1 and, on a
+// stop at k = 0, zeroes it.
+template <typename T, bool XUPD>
 __global__ void __launch_bounds__(kBlock) k_pcg_spmv(Phys ph, DevState* st, int k,
                                                      const T* __restrict__ r, const T* __restrict__ diag,
                                                      const T* __restrict__ w, const T* __restrict__ pold,
                                                      T* __restrict__ pnew, T* __restrict__ q,
-                                                     const double* part_u, double* part_s, unsigned nb,
-                                                     int fresh, int maxit) {
+                                                     T* __restrict__ x, const double* part_u,
+                                                     double* part_s, unsigned nb, int fresh, int maxit,
+                                                     int xzero) {
     MEMBER(ph)
-    if (k >= (st + mem_)->pcg.it_stop) return;
+    // it_stop == k is this launch's own decision, written by the member's
+    // first block: the other blocks must still take the stop path below
+    if (k > (st + mem_)->pcg.it_stop) return;
     double t[3];
     reduce_member<3, 0u>(part_u, nb, ph.batch, mem_, t);
     const double rz = t[0], rr = t[1];
@@ -608,12 +614,23 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(Phys ph, DevState* st, int 
             g.converged = conv ? 1 : 0;
         }
     }
-    if (stop) return;
+    const T alpha = XUPD ? (T)(st + mem_)->pcg.alpha : T(0);
+    const bool xset = XUPD && k == 1 && xzero;
+    auto xnew = [&](T xo, T po) { return xset ? alpha * po : xo + alpha * po; };
+    if (stop) {
+        if (XUPD || xzero) {
+            FOR_CELLS(ph)
+            x[P] = XUPD ? xnew(x[P], pold[P]) : T(0);
+            END_CELLS
+        }
+        return;
+    }
     const T beta = k == 0 ? T(0) : (T)(rz / (st + mem_)->pcg.rzh[(k - 1) & 1]);
     const bool first = k == 0;
     const T inv_h2 = (T)ph.inv_h2;
     double v[1] = {0.0};
     FOR_CELLS(ph)
+    if (XUPD) x[P] = xnew(x[P], pold[P]);
     auto dir = [&](size_t Q) -> T {
         T z = r[Q] / diag[Q];
         return first ? z : z + beta * pold[Q];
@@ -641,13 +658,16 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(Phys ph, DevState* st, int 
 // K = I4(w) and the direction p = z + beta p_old are read once per cell from
 // HBM: the x-y neighbours of the current plane come from LDS tiles (halo 2 for
 // w, 1 for p), the z neighbours from per-thread register queues.
-template <typename T, int RPT>
+template <typename T, int RPT, bool XUPD>
 __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     Phys ph, DevState* st, int k, const T* __restrict__ r, const T* __restrict__ diag,
     const T* __restrict__ w, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ q,
-    const double* part_u, unsigned nb_u, double* part_s, int fresh, int maxit) {
+    T* __restrict__ x, const double* part_u, unsigned nb_u, double* part_s, int fresh, int maxit,
+    int xzero) {
     MEMBER(ph)
-    if (k >= (st + mem_)->pcg.it_stop) return;
+    // it_stop == k is this launch's own decision, written by the member's
+    // first block: the other blocks must still take the stop path below
+    if (k > (st + mem_)->pcg.it_stop) return;
     double t[3];
     reduce_member<3, 0u>(part_u, nb_u, ph.batch, mem_, t);
     const double rz = t[0], rr = t[1];
@@ -670,7 +690,6 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
             g.converged = conv ? 1 : 0;
         }
     }
-    if (stop) return;
     const T beta = k == 0 ? T(0) : (T)(rz / (st + mem_)->pcg.rzh[(k - 1) & 1]);
     const bool first = k == 0;
     const T inv_h2 = (T)ph.inv_h2;
@@ -681,6 +700,23 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     const int k0 = bz_ * cz;
     const int k1 = k0 + cz < n ? k0 + cz : n;
     const size_t nn = (size_t)n * n;
+    // the previous iteration's x update (see k_pcg_spmv)
+    const T alpha = XUPD ? (T)(st + mem_)->pcg.alpha : T(0);
+    const bool xset = XUPD && k == 1 && xzero;
+    auto xnew = [&](T xo, T po) { return xset ? alpha * po : xo + alpha * po; };
+    if (stop) {
+        if (XUPD || xzero) {
+#pragma unroll
+            for (int e = 0; e < RPT; ++e) {
+                const size_t c0 = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty + e * kTY);
+                for (int kk = k0; kk < k1; ++kk) {
+                    const size_t Q = c0 + nn * (size_t)kk;
+                    x[Q] = XUPD ? xnew(x[Q], pold[Q]) : T(0);
+                }
+            }
+        }
+        return;
+    }
     __shared__ T ws[TY + 4][kTX + 4];
     __shared__ T ps[TY + 2][kTX + 2];
     auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
@@ -691,6 +727,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     size_t col[RPT];
     T wq0[RPT], wq1[RPT], wq2[RPT], wq3[RPT], wq4[RPT], pm[RPT], pc[RPT], dc[RPT];
     T rn1[RPT], dn1[RPT], on1[RPT];
+    T oc[RPT], xc[RPT], xn1[RPT];   // XUPD: raw p_old and x of the current plane, x one plane ahead
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
         col[e] = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty + e * kTY);
@@ -701,6 +738,10 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
         pm[e] = dirv(col[e] + nn * wr(k0 - 1));
         pc[e] = dirv(col[e] + nn * k0);
         dc[e] = diag[col[e] + nn * k0];
+        if (XUPD) {
+            oc[e] = pold[col[e] + nn * k0];
+            xc[e] = x[col[e] + nn * k0];
+        }
     }
     // this thread's halo cell, if any (same x-y position on every plane):
     // w rows j0-2, j0-1, j0+TY, j0+TY+1; w columns i0-2, i0-1, i0+64, i0+65;
@@ -754,11 +795,12 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     double acc = 0.0;
     for (int kk = k0; kk < k1; ++kk) {
         const size_t pl = nn * (size_t)kk;
-        T wq4c[RPT], dn[RPT], pp[RPT];
+        T wq4c[RPT], dn[RPT], pp[RPT], on[RPT];
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
             wq4c[e] = wq4[e];
             dn[e] = dn1[e];
+            on[e] = on1[e];
             pp[e] = rn1[e] / dn1[e] + beta * sel(on1[e]);
         }
         const T hwc = ha, hpc = ha / hd + beta * sel(ho);
@@ -771,6 +813,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
                 rn1[e] = r[Qf];
                 dn1[e] = diag[Qf];
                 on1[e] = pold[Qf];
+                if (XUPD) xn1[e] = x[col[e] + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk)];
             }
             ha = hsrc[Hf];
             hd = diag[Hf];
@@ -805,6 +848,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
             const T qv = (dc[e] - sumK * inv_h2) * c0 + lap * inv_h2;
             q[col[e] + pl] = qv;
             pnew[col[e] + pl] = c0;
+            if (XUPD) x[col[e] + pl] = xnew(xc[e], oc[e]);
             acc += (double)c0 * (double)qv;
         }
         lds_barrier();
@@ -817,6 +861,10 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
             pm[e] = pc[e];
             pc[e] = pp[e];
             dc[e] = dn[e];
+            if (XUPD) {
+                oc[e] = on[e];
+                xc[e] = xn1[e];
+            }
         }
     }
     double v[1] = {acc};
@@ -832,15 +880,18 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
 // loaded by wavefronts 0-5; z neighbours from per-lane register queues, the
 // lower z face coefficient carried over from the plane below.  Prefetches
 // past the chunk's last needed plane are clamped to planes already read.
-template <typename T, int V>
+template <typename T, int V, bool XUPD>
 __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     Phys ph, DevState* st, int k, const T* __restrict__ r, const T* __restrict__ diag,
     const T* __restrict__ w, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ q,
-    const double* part_u, unsigned nb_u, double* part_s, int fresh, int maxit) {
+    T* __restrict__ x, const double* part_u, unsigned nb_u, double* part_s, int fresh, int maxit,
+    int xzero) {
     using VT = T __attribute__((ext_vector_type(V)));
     static_assert(kRowWaves >= 6, "wavefronts 0-5 load the y halo rows");
     MEMBER(ph)
-    if (k >= (st + mem_)->pcg.it_stop) return;
+    // it_stop == k is this launch's own decision, written by the member's
+    // first block: the other blocks must still take the stop path below
+    if (k > (st + mem_)->pcg.it_stop) return;
     double t[3];
     reduce_member<3, 0u>(part_u, nb_u, ph.batch, mem_, t);
     const double rz = t[0], rr = t[1];
@@ -860,7 +911,6 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
             g.converged = conv ? 1 : 0;
         }
     }
-    if (stop) return;
     const T beta = k == 0 ? T(0) : (T)(rz / (st + mem_)->pcg.rzh[(k - 1) & 1]);
     const bool first = k == 0;
     const T inv_h2 = (T)ph.inv_h2;
@@ -875,8 +925,22 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     __shared__ VT pl[TY + 2][64];   // p of rows j0 - 1 .. j0 + TY
     auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
     auto ld = [](const T* f, size_t o) { return *reinterpret_cast<const VT*>(f + o); };
+    auto st_v = [](T* f, size_t o, VT v) { *reinterpret_cast<VT*>(f + o) = v; };
     auto sel = [&](VT v) { return first ? VT(T(0)) : v; };
     const size_t col = base_ + (size_t)n * (j0 + wv) + (size_t)V * lane;
+    // the previous iteration's x update (see k_pcg_spmv)
+    const T alpha = XUPD ? (T)(st + mem_)->pcg.alpha : T(0);
+    const bool xset = XUPD && k == 1 && xzero;
+    auto xnew = [&](VT xo, VT po) { return xset ? alpha * po : xo + alpha * po; };
+    if (stop) {
+        if (XUPD || xzero) {
+            for (int kk = k0; kk < k1; ++kk) {
+                const size_t Q = col + nn * (size_t)kk;
+                st_v(x, Q, XUPD ? xnew(ld(x, Q), ld(pold, Q)) : VT(T(0)));
+            }
+        }
+        return;
+    }
     // this wavefront's y halo row: w rows j0-2, j0-1, j0+TY, j0+TY+1 (waves
     // 0-3), p rows j0-1, j0+TY (waves 4-5, from r, diag and p_old); waves 6..
     // read their own row so that every load is unconditional
@@ -889,7 +953,9 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     VT wm1 = ld(w, col + plane(k0 - 1)), w0 = ld(w, col + plane(k0)), wp1 = ld(w, col + plane(k0 + 1));
     VT wp2n = ld(w, col + plane(k0 + 2));
     VT pm = ld(r, col + plane(k0 - 1)) / ld(diag, col + plane(k0 - 1)) + beta * sel(ld(pold, col + plane(k0 - 1)));
-    VT pc = ld(r, col + plane(k0)) / ld(diag, col + plane(k0)) + beta * sel(ld(pold, col + plane(k0)));
+    VT oc = ld(pold, col + plane(k0));   // raw p_old of the current plane (x update)
+    VT pc = ld(r, col + plane(k0)) / ld(diag, col + plane(k0)) + beta * sel(oc);
+    VT xc = XUPD ? ld(x, col + plane(k0)) : VT(T(0)), xn1 = xc;
     VT dc = ld(diag, col + plane(k0));
     VT rnx = ld(r, col + plane(k0 + 1)), dnx = ld(diag, col + plane(k0 + 1)), onx = ld(pold, col + plane(k0 + 1));
     VT h1 = ld(hsrc, hcol + plane(k0)), h2 = ld(diag, hcol + plane(k0)), h3 = ld(pold, hcol + plane(k0));
@@ -900,7 +966,7 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     for (int kk = k0; kk < k1; ++kk) {
         const VT wp2 = wp2n;
         const VT pp = rnx / dnx + beta * sel(onx);
-        const VT dn = dnx;
+        const VT dn = dnx, on = onx;
         const VT hw = h1, hp = h1 / h2 + beta * sel(h3);
         {
             const int kw = kk + 3 < k1 + 1 ? kk + 3 : k1 + 1;   // last w plane needed: k1 + 1
@@ -913,6 +979,7 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
             h1 = ld(hsrc, hcol + plane(kh));
             h2 = ld(diag, hcol + plane(kh));
             h3 = ld(pold, hcol + plane(kh));
+            if (XUPD) xn1 = ld(x, col + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk));
         }
         wl[wv + 2][lane] = w0;
         pl[wv + 1][lane] = pc;
@@ -957,8 +1024,13 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
             acc += (double)c0 * (double)qv;
         }
         const size_t pl0 = nn * (size_t)kk;
-        *reinterpret_cast<VT*>(q + col + pl0) = qo;
-        *reinterpret_cast<VT*>(pnew + col + pl0) = pc;
+        st_v(q, col + pl0, qo);
+        st_v(pnew, col + pl0, pc);
+        if (XUPD) {
+            st_v(x, col + pl0, xnew(xc, oc));
+            xc = xn1;
+            oc = on;
+        }
         wm1 = w0;
         w0 = wp1;
         wp1 = wp2;
@@ -972,22 +1044,24 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
 }
 
 // Iteration k, second half: alpha_k = r_k.z_k / p_k.q from the previous
-// kernel's partials, x += alpha p, r -= alpha q, and partial sums of
-// r.(r/diag) and r.r for the next first half.
+// kernel's partials, r -= alpha q, and partial sums of r.(r/diag) and r.r
+// for the next first half.  x += alpha p is left to that first half (it
+// reads p_k anyway): alpha_k goes to the member state.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_pcg_update(Phys ph, const DevState* st, int k,
+__global__ void __launch_bounds__(kBlock) k_pcg_update(Phys ph, DevState* st, int k,
                                                        T* __restrict__ r, const T* __restrict__ q,
-                                                       const T* __restrict__ diag, T* __restrict__ x,
-                                                       const T* __restrict__ p, const double* part_s,
-                                                       double* part_u, unsigned nb_s) {
+                                                       const T* __restrict__ diag,
+                                                       const double* part_s, double* part_u,
+                                                       unsigned nb_s) {
     MEMBER(ph)
     if (k >= (st + mem_)->pcg.it_stop) return;
     double pq[1];
     reduce_member<1, 0u>(part_s, nb_s, ph.batch, mem_, pq);
-    const T alpha = (T)((st + mem_)->pcg.rzh[k & 1] / pq[0]);
+    const double alpha64 = (st + mem_)->pcg.rzh[k & 1] / pq[0];
+    const T alpha = (T)alpha64;
+    if (MEMBER_FIRST()) (st + mem_)->pcg.alpha = alpha64;
     double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
-    x[P] += alpha * p[P];
     const T rn = r[P] - alpha * q[P];
     r[P] = rn;
     v[0] += (double)rn * ((double)rn / (double)diag[P]);
@@ -1671,9 +1745,9 @@ Launch make_tiled_launch(int n, int batch) {
     return L;
 }
 
-Launch make_spmv_launch(int n, int batch) {
+Launch make_spmv_launch(int n, int batch, int elem_bytes) {
     Launch L{};
-    if (n == 64 * kRowCells) {   // full-row form
+    if (n == 64 * kRowCells && elem_bytes == 4) {   // full-row form
         const int gy = n / kRowWaves;
         int nz = kRowBlocks / gy;
         nz = nz < 1 ? 1 : nz;
@@ -1781,48 +1855,68 @@ void Ops<T>::hbya(const Launch& L, const Launch& TL, hipStream_t s, const Phys& 
 }
 template <typename T>
 void Ops<T>::corr_rhs(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, const T* rn,
-                      const T* rk, const T* w, const T* hb, const T* p0, T* phiH, T* r, T* x,
-                      T* diag, double* part_u, double* snap_b, double* snap_diag,
-                      double* snap_p0, double* b64, double* x64) {
-    LAUNCH(k_corr_rhs<T>, L, s, ph, st, rn, rk, w, hb, p0, phiH, r, x, diag, part_u, snap_b,
-           snap_diag, snap_p0, b64, x64);
+                      const T* rk, const T* w, const T* hb, const T* p0, T* phiH, T* r, T* diag,
+                      double* part_u, double* snap_b, double* snap_diag, double* snap_p0,
+                      double* b64) {
+    LAUNCH(k_corr_rhs<T>, L, s, ph, st, rn, rk, w, hb, p0, phiH, r, diag, part_u, snap_b,
+           snap_diag, snap_p0, b64);
 }
 template <typename T>
 void Ops<T>::refine(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                     const double* x64, const T* d, double* x64n, const double* b64, const T* w,
-                    const T* diag, T* r32, double* part_u) {
-    LAUNCH(k_refine<T>, L, s, ph, st, x64, d, x64n, b64, w, diag, r32, part_u);
+                    const T* diag, T* r32, double* part_u, bool from_zero) {
+    if (from_zero)
+        LAUNCH((k_refine<T, true>), L, s, ph, st, x64, d, x64n, b64, w, diag, r32, part_u);
+    else
+        LAUNCH((k_refine<T, false>), L, s, ph, st, x64, d, x64n, b64, w, diag, r32, part_u);
 }
 template <typename T>
 void Ops<T>::zero(hipStream_t s, T* a, size_t count) {
     hipLaunchKernelGGL(k_zero<T>, lin_grid(count), dim3(kBlock), 0, s, a, count);
 }
-template <typename T>
-void Ops<T>::pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
-                      DevState* st, int k, const T* r, const T* diag, const T* w, const T* pold,
-                      T* pnew, T* q, const double* part_u, double* part_s, int fresh, int maxit) {
-    if (TL.nblocks && TL.v == kRowCells) {
+template <typename T, bool XUPD>
+static void spmv_launch(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                        DevState* st, int k, const T* r, const T* diag, const T* w, const T* pold,
+                        T* pnew, T* q, T* x, const double* part_u, double* part_s, int fresh,
+                        int maxit, int xzero) {
+    if constexpr (sizeof(T) == 4) {
+        if (TL.nblocks && TL.v == kRowCells) {
+            Phys pt = ph;
+            pt.cz = TL.cz;
+            pt.nz = TL.nz;
+            LAUNCH((k_pcg_spmv_rows<T, kRowCells, XUPD>), TL, s, pt, st, k, r, diag, w, pold, pnew, q,
+                   x, part_u, L.nblocks, part_s, fresh, maxit, xzero);
+            return;
+        }
+    }
+    if (TL.nblocks) {
         Phys pt = ph;
         pt.cz = TL.cz;
         pt.nz = TL.nz;
-        LAUNCH((k_pcg_spmv_rows<T, kRowCells>), TL, s, pt, st, k, r, diag, w, pold, pnew, q, part_u,
-               L.nblocks, part_s, fresh, maxit);
-    } else if (TL.nblocks) {
-        Phys pt = ph;
-        pt.cz = TL.cz;
-        pt.nz = TL.nz;
-        LAUNCH((k_pcg_spmv_tiled<T, kSpmvRows>), TL, s, pt, st, k, r, diag, w, pold, pnew, q, part_u,
-               L.nblocks, part_s, fresh, maxit);
+        LAUNCH((k_pcg_spmv_tiled<T, kSpmvRows, XUPD>), TL, s, pt, st, k, r, diag, w, pold, pnew, q,
+               x, part_u, L.nblocks, part_s, fresh, maxit, xzero);
     } else {
-        LAUNCH(k_pcg_spmv<T>, L, s, ph, st, k, r, diag, w, pold, pnew, q, part_u, part_s,
-               L.nblocks, fresh, maxit);
+        LAUNCH((k_pcg_spmv<T, XUPD>), L, s, ph, st, k, r, diag, w, pold, pnew, q, x, part_u, part_s,
+               L.nblocks, fresh, maxit, xzero);
     }
 }
 template <typename T>
+void Ops<T>::pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                      DevState* st, int k, const T* r, const T* diag, const T* w, const T* pold,
+                      T* pnew, T* q, T* x, const double* part_u, double* part_s, int fresh,
+                      int maxit, int xzero) {
+    if (k == 0)
+        spmv_launch<T, false>(L, TL, s, ph, st, k, r, diag, w, pold, pnew, q, x, part_u, part_s,
+                              fresh, maxit, xzero);
+    else
+        spmv_launch<T, true>(L, TL, s, ph, st, k, r, diag, w, pold, pnew, q, x, part_u, part_s,
+                             fresh, maxit, xzero);
+}
+template <typename T>
 void Ops<T>::pcg_update(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
-                        const DevState* st, int k, T* r, const T* q, const T* diag, T* x,
-                        const T* p, const double* part_s, double* part_u) {
-    LAUNCH(k_pcg_update<T>, L, s, ph, st, k, r, q, diag, x, p, part_s, part_u,
+                        DevState* st, int k, T* r, const T* q, const T* diag,
+                        const double* part_s, double* part_u) {
+    LAUNCH(k_pcg_update<T>, L, s, ph, st, k, r, q, diag, part_s, part_u,
            TL.nblocks ? TL.nblocks : L.nblocks);
 }
 template <typename T>

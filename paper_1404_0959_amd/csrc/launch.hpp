@@ -35,14 +35,15 @@ Launch make_launch_shaped(int n, int batch, int bx, int cz);
 // is 0 when n is not a multiple of the tile or below 128.
 Launch make_tiled_launch(int n, int batch = 1);
 
-// Launch of the CG first half.  For n = 64 kRowCells: the full-row form, blocks
-// of kRowWaves wavefronts each owning one x-row (kRowCells cells per lane),
-// about kRowBlocks blocks per member (v = kRowCells).  Otherwise tiles of
-// 64 x (8 kSpmvRows) cells, 64 x 8 threads each owning kSpmvRows rows
-// (v = 0); nblocks is 0 when neither is available.
+// Launch of the CG first half for fields of elem_bytes per value.  For
+// n = 64 kRowCells and FP32: the full-row form, blocks of kRowWaves
+// wavefronts each owning one x-row (kRowCells cells per lane), about
+// kRowBlocks blocks per member (v = kRowCells; in FP64 its registers would
+// not fit).  Otherwise tiles of 64 x (8 kSpmvRows) cells, 64 x 8 threads each
+// owning kSpmvRows rows (v = 0); nblocks is 0 when neither is available.
 constexpr int kSpmvRows = 1;
 constexpr int kRowCells = 4, kRowWaves = 8, kRowBlocks = 256;
-Launch make_spmv_launch(int n, int batch = 1);
+Launch make_spmv_launch(int n, int batch, int elem_bytes);
 
 // Partial-sum slots in the workspace (columns of num_blocks doubles each).
 enum PartSlot {
@@ -79,22 +80,26 @@ struct Ops {
     static void hbya(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                      const DevState* st, const T* uin, T* hb, const T* phi, const T* aP,
                      const T* src, const T* rk, T* w, T* p0);
+    // CG starts from x = 0 without x being written (see pcg_spmv's xzero)
     static void corr_rhs(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                          const T* rn, const T* rk, const T* w, const T* hb, const T* p0, T* phiH,
-                         T* r, T* x, T* diag, double* part_u, double* snap_b, double* snap_diag,
-                         double* snap_p0, double* b64, double* x64);
+                         T* r, T* diag, double* part_u, double* snap_b, double* snap_diag,
+                         double* snap_p0, double* b64);
+    // from_zero: x64 is zero and not read (first round of a solve from zero)
     static void refine(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                        const double* x64, const T* d, double* x64n, const double* b64,
-                       const T* w, const T* diag, T* r32, double* part_u);
+                       const T* w, const T* diag, T* r32, double* part_u, bool from_zero);
     static void zero(hipStream_t s, T* a, size_t count);
     // TL: the tiled CG launch of make_spmv_launch (used when TL.nblocks > 0)
+    // k >= 1 also applies the previous iteration's x += alpha p; xzero: the
+    // solve started from x = 0 without x being written
     static void pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                          DevState* st, int k, const T* r, const T* diag, const T* w,
-                         const T* pold, T* pnew, T* q, const double* part_u, double* part_s,
-                         int fresh, int maxit);
+                         const T* pold, T* pnew, T* q, T* x, const double* part_u,
+                         double* part_s, int fresh, int maxit, int xzero);
     static void pcg_update(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
-                           const DevState* st, int k, T* r, const T* q, const T* diag, T* x,
-                           const T* p, const double* part_s, double* part_u);
+                           DevState* st, int k, T* r, const T* q, const T* diag,
+                           const double* part_s, double* part_u);
     static void helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt,
                            const T* w, const T* x, T* y);
     static void helm_start(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,

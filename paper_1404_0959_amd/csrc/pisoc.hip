@@ -153,7 +153,7 @@ Layout make_layout(const pisoc_params* p, int batch) {
     const size_t N = (size_t)p->n * p->n * p->n * (size_t)batch;
     const size_t es = p->precision == PISOC_FP64 ? sizeof(double) : sizeof(float);
     unsigned mb = std::max({make_launch(p->n, batch).nblocks, make_tiled_launch(p->n, batch).nblocks,
-                            make_spmv_launch(p->n, batch).nblocks});
+                            make_spmv_launch(p->n, batch, (int)es).nblocks});
     for (auto [bx, cz] : shape_candidates(p->n))
         mb = std::max(mb, make_launch_shaped(p->n, batch, bx, cz).nblocks);
     L.max_blocks = mb;
@@ -314,22 +314,24 @@ void set_shape(pisoc_ctx* ctx, const Launch& L) {
 // `pairs` pairs (capture).  Returns the largest iteration count (eager).
 template <typename T>
 pisoc_status run_pcg(pisoc_ctx* ctx, T* r, T* x, T* diag, T* w, T* pp0, T* pp1, T* q, bool fresh,
-                     int pairs, bool eager, int* iters_max) {
+                     int pairs, bool eager, int* iters_max, bool xzero) {
     using O = Ops<T>;
     const int maxit = ctx->prm.p_maxit;
     T* pp[2] = {pp0, pp1};
     double* pu = ctx->part(PS_U);
     double* ps = ctx->part(PS_S);
     auto spmv = [&](int k) {
-        timed(ctx, KC_PCG_SPMV, k == 0 ? 5.0 : 6.0, k, [&] {
+        // words: r, diag, w read, p, q written; from k = 1 also p_old read and x updated
+        timed(ctx, KC_PCG_SPMV, k == 0 ? 5.0 : 8.0, k, [&] {
             O::pcg_spmv(ctx->L, ctx->TS, ctx->stream, ctx->ph, ctx->st, k, r, diag, w,
-                        pp[(k + 1) & 1], pp[k & 1], q, pu, ps, fresh ? 1 : 0, maxit);
+                        pp[(k + 1) & 1], pp[k & 1], q, x, pu, ps, fresh ? 1 : 0, maxit,
+                        xzero ? 1 : 0);
         });
     };
     auto update = [&](int k) {
-        timed(ctx, KC_PCG_UPDATE, 7.0, k, [&] {
-            O::pcg_update(ctx->L, ctx->TS, ctx->stream, ctx->ph, ctx->st, k, r, q, diag, x, pp[k & 1],
-                          ps, pu);
+        // words: r, q, diag read, r written
+        timed(ctx, KC_PCG_UPDATE, 4.0, k, [&] {
+            O::pcg_update(ctx->L, ctx->TS, ctx->stream, ctx->ph, ctx->st, k, r, q, diag, ps, pu);
         });
     };
     spmv(0);
@@ -488,10 +490,10 @@ void enqueue_corr_setup(pisoc_ctx* ctx, StepPtrs<T>& S, int corr, bool guess) {
     timed(ctx, KC_HBYA, 16, -1,
           [&] { O::hbya(L, ctx->TL, s, ph, ctx->st, ucur, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0); });
     const bool cap = S.snap && corr == 0;
-    timed(ctx, KC_CORR_RHS, f32 ? 17 : 13, -1, [&] {
-        O::corr_rhs(L, s, ph, ctx->st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH, S.r, S.x, S.dg,
+    timed(ctx, KC_CORR_RHS, f32 ? 14 : 12, -1, [&] {
+        O::corr_rhs(L, s, ph, ctx->st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH, S.r, S.dg,
                     ctx->part(PS_U), cap ? S.snap : nullptr, cap ? S.snap + N : nullptr,
-                    cap ? S.snap + 2 * N : nullptr, S.b64, S.x64a);
+                    cap ? S.snap + 2 * N : nullptr, S.b64);
     });
     if (guess) learned_guess<T>(ctx, S.r, S.x, S.dg, S.w, S.p0, S.pp0, S.q);
 }
@@ -548,7 +550,8 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
 }
 
 // FP32 storage: mixed-precision iterative refinement of M p' = b for every
-// member.  The first inner FP32 solve runs to tau0 = max(p_tol/2, inner_tol)
+// member.  guess: the first inner solve starts from the learned guess (x and
+// x64 set), else from zero.  The first inner FP32 solve runs to tau0 = max(p_tol/2, inner_tol)
 // of ||b||; after each inner solve k_refine adds the correction to the FP64
 // accumulator and evaluates the true residual in FP64; each later round aims
 // at half the requested residual (reducing the current one by no more than
@@ -556,7 +559,8 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
 // eager: rounds until every member is done or max_refine; otherwise exactly
 // ctx->rounds rounds with ctx->caps / cap_later CG pairs.  The FP64 solution
 // ends in x64a and its FP32 copy in x.
-void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool eager, pisoc_status* err) {
+void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool eager,
+                pisoc_status* err) {
     const pisoc_params& p = ctx->prm;
     hipStream_t s = ctx->stream;
     const int B = ctx->batch;
@@ -568,16 +572,17 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool eager, pisoc_
     int most = 0;
     const int pairs0 = eager ? (ctx->pred_first[corr] > 0 ? ctx->pred_first[corr] : 8) : ctx->caps[corr];
     if ((*err = run_pcg<float>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, true, pairs0, eager,
-                               &most)) != PISOC_OK)
+                               &most, !guess)) != PISOC_OK)
         return;
     if (eager) ctx->pred_first[corr] = most;
     record_solve(s, ctx->st, B, corr, /*round=*/1, /*add=*/1, /*fin=*/0);
     const int max_rounds = eager ? p.max_refine : ctx->rounds;
     int round = 0;
     for (;;) {
-        timed(ctx, KC_REFINE, 10, -1, [&] {
+        const bool from_zero = round == 0 && !guess;
+        timed(ctx, KC_REFINE, from_zero ? 8 : 10, -1, [&] {
             Ops<float>::refine(ctx->L, s, ctx->ph, ctx->st, xa, S.x, xb, S.b64, S.w, S.dg, S.r,
-                               ctx->part(PS_U));
+                               ctx->part(PS_U), from_zero);
         });
         std::swap(xa, xb);
         ++round;
@@ -595,10 +600,10 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool eager, pisoc_
             if (done) break;
         }
         set_tol_refine(s, ctx->st, B, p.inner_tol);
-        Ops<float>::zero(s, S.x, ctx->NT());
+        // the inner correction of this round starts from zero (not written)
         const int pairs = eager ? std::max(2, ctx->pred_later) : ctx->cap_later;
         if ((*err = run_pcg<float>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, false, pairs, eager,
-                                   &most)) != PISOC_OK)
+                                   &most, true)) != PISOC_OK)
             return;
         if (eager) ctx->pred_later = most;
         record_solve(s, ctx->st, B, corr, round + 1, /*add=*/1, /*fin=*/0);
@@ -667,13 +672,14 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
         if (audit && guess) (void)hipEventRecord(ctx->audit.ev[corr][1], s);
         pisoc_status err = PISOC_OK;
         if constexpr (sizeof(T) == sizeof(float)) {
-            solve_fp32(ctx, S, corr, eager, &err);
+            solve_fp32(ctx, S, corr, guess, eager, &err);
         } else {
             set_tol(s, ctx->st, ctx->batch, p.p_tol * p.p_tol);
             int most = 0;
             const int pairs =
                 eager ? (ctx->pred_first[corr] > 0 ? ctx->pred_first[corr] : 8) : ctx->caps[corr];
-            err = run_pcg<T>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, true, pairs, eager, &most);
+            err = run_pcg<T>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, true, pairs, eager, &most,
+                             !guess);
             if (eager) ctx->pred_first[corr] = most;
             record_solve(s, ctx->st, ctx->batch, corr, /*round=*/0, /*add=*/1, /*fin=*/1);
         }
@@ -799,7 +805,7 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     ctx->lay = make_layout(prm, batch);
     const Layout& lay = ctx->lay;
     ctx->TL = make_tiled_launch(prm->n, batch);
-    ctx->TS = make_spmv_launch(prm->n, batch);
+    ctx->TS = make_spmv_launch(prm->n, batch, prm->precision == PISOC_FP64 ? 8 : 4);
     // PISOC_UNTILED=1 selects the untiled kernels (kernel-comparison tests)
     if (const char* e = std::getenv("PISOC_UNTILED"); e && e[0] == '1') ctx->TL = ctx->TS = Launch{};
     ctx->L = make_launch(prm->n, batch);
@@ -1111,15 +1117,14 @@ void enqueue_probe(pisoc_ctx* ctx) {
     DevState* st = ctx->st;
     O::mom_sweep(L, ctx->TL, s, ph, st, S.un, S.ua, S.phin, S.aP, S.src, S.pn);
     O::hbya(L, ctx->TL, s, ph, st, S.ua, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0);
-    O::corr_rhs(L, s, ph, st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH, S.r, S.x, S.dg, ctx->part(PS_U),
-                nullptr, nullptr, nullptr, S.b64, S.x64a);
+    O::corr_rhs(L, s, ph, st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH, S.r, S.dg, ctx->part(PS_U),
+                nullptr, nullptr, nullptr, S.b64);
     // two CG iterations that cannot stop early (tolerance 0, maxit above 2)
     set_tol(s, st, ctx->batch, 0.0);
     for (int k = 0; k < 2; ++k) {
         O::pcg_spmv(L, ctx->TS, s, ph, st, k, S.r, S.dg, S.w, k ? S.pp0 : S.pp1, k ? S.pp1 : S.pp0,
-                    S.q, ctx->part(PS_U), ctx->part(PS_S), 1, 1 << 20);
-        O::pcg_update(L, ctx->TS, s, ph, st, k, S.r, S.q, S.dg, S.x, k ? S.pp1 : S.pp0,
-                      ctx->part(PS_S), ctx->part(PS_U));
+                    S.q, S.x, ctx->part(PS_U), ctx->part(PS_S), 1, 1 << 20, 1);
+        O::pcg_update(L, ctx->TS, s, ph, st, k, S.r, S.q, S.dg, ctx->part(PS_S), ctx->part(PS_U));
     }
     if (ctx->prm.n_classes > 0) O::dust_sweep(L, s, ph, st, S.Ya, S.Yb, S.G, S.rj, S.rk);
 }
@@ -1716,7 +1721,7 @@ static Layout helm_layout(int32_t n) {
     Layout L{};
     const size_t N = (size_t)n * n * n;
     L.max_blocks = std::max({make_launch(n, 1).nblocks, make_tiled_launch(n, 1).nblocks,
-                             make_spmv_launch(n, 1).nblocks});
+                             make_spmv_launch(n, 1, 8).nblocks});
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     L.state = take(sizeof(DevState));
@@ -1774,9 +1779,7 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
     ctx.lay = lay;
     ctx.L = make_launch(n, 1);
     ctx.TL = make_tiled_launch(n, 1);
-    ctx.TS = make_spmv_launch(n, 1);
-    // the full-row CG kernel reads w with vector loads of kRowCells doubles
-    if (reinterpret_cast<uintptr_t>(d_w) % (kRowCells * sizeof(double)) != 0 && ctx.TS.v) ctx.TS = Launch{};
+    ctx.TS = make_spmv_launch(n, 1, sizeof(double));
     ctx.ph = make_phys(&ctx.prm, ctx.L, 1);
     ctx.es = sizeof(double);
     ctx.st = reinterpret_cast<DevState*>(ctx.ws + lay.state);
@@ -1802,7 +1805,8 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
         Ops<double>::helm_start(ctx.L, ctx.stream, ctx.ph, ctx.st, d_psidt, d_w, d_b, d_x, r, dg,
                                 ctx.part(PS_U));
         st = run_pcg<double>(&ctx, r, d_x, dg, const_cast<double*>(d_w), ctx.f<double>(lay.pp0),
-                             ctx.f<double>(lay.pp1), ctx.f<double>(lay.q), true, 16, true, nullptr);
+                             ctx.f<double>(lay.pp1), ctx.f<double>(lay.q), true, 16, true, nullptr,
+                             false);
         if (st == PISOC_OK) {
             const PcgState& g = ctx.hst->pcg;
             if (iters) *iters = g.iters;

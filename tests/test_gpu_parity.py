@@ -87,7 +87,7 @@ def test_helm_apply_parity(P, ora, n):
 
 @pytest.mark.parametrize("n", [16, 40, 128, 256])
 def test_helm_solve_parity(P, ora, n):
-    """128 runs the 64 x 8 tiled CG first half, 256 the full-row form."""
+    """128 and 256 run the 64 x 8 tiled CG first half (FP64)."""
     import torch
     rng = np.random.default_rng(100 + n)
     h = 2 * math.pi / n
@@ -172,7 +172,7 @@ def test_step_parity_hit128_tiled(P, ora):
 def test_step_parity_hit256_bench_workload(P, ora):
     """One step of the 256^3 workload the benchmark times (decaying HIT, Mach
     0.2, one class at Stokes 0.2, residual 1e-6), in its launch configuration:
-    the full-row CG kernel and the LDS-tiled momentum sweeps."""
+    the tiled CG kernel and the LDS-tiled momentum sweeps."""
     case = make_hit_case(256, 0, mach=0.2, stokes=(0.2,))
     o, s, io, ig = run_pair(P, ora, case, 1, p_tol=1e-6)
     compare_state(P, ora, s, o)
