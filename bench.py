@@ -180,12 +180,15 @@ def ensemble_run(P, torch, args, weights):
 
 
 KERNEL_SOURCES = ("kernels.hip", "device.hpp", "launch.hpp", "net.hip")
-# dominant kernel class -> the 256^3 kernel whose HBM bytes the committed
-# counter summary holds
-TRAFFIC_NAME = {("k_pcg_spmv", "f32+f64"): "k_pcg_spmv_rows<float, 4>",
-                ("k_pcg_spmv", "f64"): "k_pcg_spmv_rows<double, 4>",
-                ("k_pcg_update", "f32+f64"): "k_pcg_update<float>",
-                ("k_pcg_update", "f64"): "k_pcg_update<double>"}
+# dominant kernel class -> the 256^3 kernels whose HBM bytes the committed
+# counter summary holds (template instances of one kernel class are averaged
+# over their working launches)
+TRAFFIC_NAME = {("k_pcg_spmv", "f32+f64"): ("k_pcg_spmv_rows<float, 4, false>",
+                                           "k_pcg_spmv_rows<float, 4, true>"),
+                ("k_pcg_spmv", "f64"): ("k_pcg_spmv_tiled<double, 1, false>",
+                                       "k_pcg_spmv_tiled<double, 1, true>"),
+                ("k_pcg_update", "f32+f64"): ("k_pcg_update<float>",),
+                ("k_pcg_update", "f64"): ("k_pcg_update<double>",)}
 
 
 def measured_traffic(kernel, dtype, n):
@@ -205,8 +208,13 @@ def measured_traffic(kernel, dtype, n):
             h.update(f.read())
     if h.hexdigest() != rec.get("source_sha256"):
         return None
-    k = rec["kernels"].get(TRAFFIC_NAME.get((kernel, dtype), ""))
-    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+    recs = [rec["kernels"].get(name) for name in TRAFFIC_NAME.get((kernel, dtype), ())]
+    if not recs or any(r is None for r in recs):
+        return None
+    launches = sum(r["launches"] for r in recs)
+    if launches == 0:
+        return None
+    return sum((r["fetch_bytes"] + r["write_bytes"]) * r["launches"] for r in recs) / launches
 
 
 def roofline(prof):

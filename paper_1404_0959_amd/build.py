@@ -20,7 +20,6 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["kernels.hip", "pisoc.hip", "net.hip"]
-EXTRA_SOURCES = ["ensemble.hip"]   # compiled when present
 
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-I", INCLUDE,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -28,9 +27,7 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-I", INCLUDE,
 
 
 def sources():
-    out = [os.path.join(CSRC, s) for s in SOURCES]
-    out += [os.path.join(CSRC, s) for s in EXTRA_SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    return out
+    return [os.path.join(CSRC, s) for s in SOURCES]
 
 
 def _compile(src: str) -> str:

@@ -1046,27 +1046,56 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
 // Iteration k, second half: alpha_k = r_k.z_k / p_k.q from the previous
 // kernel's partials, r -= alpha q, and partial sums of r.(r/diag) and r.r
 // for the next first half.  x += alpha p is left to that first half (it
-// reads p_k anyway): alpha_k goes to the member state.
+// reads p_k anyway): alpha_k goes to the member state.  The work is
+// pointwise, so the launch is flat: per_member blocks per member (the block
+// count of the stencil launch whose partials the first half also reads),
+// block c of member m streaming one contiguous chunk of its cells, four
+// cells per thread and load when N is a multiple of 4.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_pcg_update(Phys ph, DevState* st, int k,
                                                        T* __restrict__ r, const T* __restrict__ q,
                                                        const T* __restrict__ diag,
                                                        const double* part_s, double* part_u,
-                                                       unsigned nb_s) {
-    MEMBER(ph)
+                                                       unsigned nb_s, unsigned per_member) {
+    using V4 = T __attribute__((ext_vector_type(4)));
+    const unsigned id = flat_bid();
+    const int mem_ = (int)(id / per_member);
+    const unsigned chunk = id - (unsigned)mem_ * per_member;
     if (k >= (st + mem_)->pcg.it_stop) return;
     double pq[1];
     reduce_member<1, 0u>(part_s, nb_s, ph.batch, mem_, pq);
     const double alpha64 = (st + mem_)->pcg.rzh[k & 1] / pq[0];
     const T alpha = (T)alpha64;
-    if (MEMBER_FIRST()) (st + mem_)->pcg.alpha = alpha64;
+    if (chunk == 0 && threadIdx.x == 0) (st + mem_)->pcg.alpha = alpha64;
+    const size_t N = ph.N;
+    const size_t C = (((N + per_member - 1) / per_member) + 3) & ~(size_t)3;   // cells per block
+    const size_t beg = (size_t)chunk * C < N ? (size_t)chunk * C : N;
+    const size_t end = beg + C < N ? beg + C : N;
+    const size_t base = (size_t)mem_ * N;
     double v[3] = {0.0, 0.0, 0.0};
-    FOR_CELLS(ph)
-    const T rn = r[P] - alpha * q[P];
-    r[P] = rn;
-    v[0] += (double)rn * ((double)rn / (double)diag[P]);
-    v[1] += (double)rn * (double)rn;
-    END_CELLS
+    auto cell = [&](T rv, T qv, T dv) {
+        const T rn = rv - alpha * qv;
+        v[0] += (double)rn * ((double)rn / (double)dv);
+        v[1] += (double)rn * (double)rn;
+        return rn;
+    };
+    if (N % 4 == 0) {   // beg, end and base are multiples of 4: aligned vectors
+        for (size_t i = beg + 4 * (size_t)threadIdx.x; i < end; i += 4 * (size_t)blockDim.x) {
+            const size_t P = base + i;
+            const V4 rv = *reinterpret_cast<const V4*>(r + P);
+            const V4 qv = *reinterpret_cast<const V4*>(q + P);
+            const V4 dv = *reinterpret_cast<const V4*>(diag + P);
+            V4 rn;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rn[e] = cell(rv[e], qv[e], dv[e]);
+            *reinterpret_cast<V4*>(r + P) = rn;
+        }
+    } else {
+        for (size_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+            const size_t P = base + i;
+            r[P] = cell(r[P], q[P], diag[P]);
+        }
+    }
     block_partials<3, 0u>(v, part_u);
 }
 
@@ -1916,8 +1945,10 @@ template <typename T>
 void Ops<T>::pcg_update(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                         DevState* st, int k, T* r, const T* q, const T* diag,
                         const double* part_s, double* part_u) {
-    LAUNCH(k_pcg_update<T>, L, s, ph, st, k, r, q, diag, part_s, part_u,
-           TL.nblocks ? TL.nblocks : L.nblocks);
+    // flat launch with the stencil launch's block count and member layout
+    hipLaunchKernelGGL(k_pcg_update<T>, dim3(L.nblocks), dim3(kBlock), 0, s, ph, st, k, r, q, diag,
+                       part_s, part_u, TL.nblocks ? TL.nblocks : L.nblocks,
+                       L.nblocks / (unsigned)ph.batch);
 }
 template <typename T>
 void Ops<T>::helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt, const T* w,
