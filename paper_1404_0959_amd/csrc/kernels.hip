@@ -445,28 +445,16 @@ __global__ void __launch_bounds__(kTX * kTY) k_mom_sweep_tiled(
 // x update writes rather than adds).  With b64 non-null (FP32 storage) the
 // FP64 defect is also kept (the first refinement takes the FP64 accumulator
 // as zero).
+
+// The per-cell arithmetic of the corrector set-up, shared by the gathered and
+// the tiled kernel: from w and rho_k on the 13-point cross, the HbyA component
+// d on the line along d, p0 on the 7-point cross and rho^n of the cell, the
+// predicted fluxes on the cell's own faces phf, the FP64 defect b and diag(M).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_corr_rhs(
-    Phys ph, DevState* st, const T* __restrict__ rn, const T* __restrict__ rk,
-    const T* __restrict__ w, const T* __restrict__ hbya, const T* __restrict__ p0,
-    T* __restrict__ phiH, T* __restrict__ rvec, T* __restrict__ diag, double* part_u,
-    double* snap_b, double* snap_diag, double* snap_p0, double* b64) {
-    MEMBER(ph)
-    const size_t N = ncell(ph);
-    const double dt = (st + mem_)->dt;
-    const double A = ph.A, inv_V = ph.inv_V, inv_h = ph.inv_h, inv_h2 = ph.inv_h2;
-    const double rref = (st + mem_)->rho_ref;
-    double v[3] = {0.0, 0.0, 0.0};
-    FOR_CELLS(ph)
-    // every load of the cell first, then the FP64 arithmetic
-    T wv[13], rv[13], hl[3][5], pv[7];
-    gather13(w, c, wv);
-    gather13(rk, c, rv);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) gather_line(hbya + d * N, c, d, hl[d]);
-    gather7(p0, c, pv);
-    const T rnP = rn[P];
-    loads_issued();
+__device__ inline void corr_rhs_cell(const T (&wv)[13], const T (&rv)[13], const T (&hl)[3][5],
+                                     const T (&pv)[7], T rnP, double dt, double rref, double pref,
+                                     double gamma, double A, double inv_V, double inv_h,
+                                     double inv_h2, double& b, T& dgT, T (&phf)[3]) {
     double divF = 0.0, sumK = 0.0;
     const double p0P = (double)pv[0];
 #pragma unroll
@@ -480,13 +468,23 @@ __global__ void __launch_bounds__(kBlock) k_corr_rhs(
             const double F = ph_f - Kf * A * sn;
             divF += s == 0 ? F : -F;
             sumK += Kf;
-            if (s == 0) phiH[d * N + P] = (T)ph_f;
+            if (s == 0) phf[d] = (T)ph_f;
         }
     }
-    const double b = -(((double)rv[0] - (double)rnP) / dt + divF * inv_V);
+    b = -(((double)rv[0] - (double)rnP) / dt + divF * inv_V);
     const double rho = rref + (double)rv[0];
-    const double psidt = rho / (ph.gamma * ((st + mem_)->p_ref + p0P)) / dt;
-    const T dgT = (T)(psidt + sumK * inv_h2);
+    const double psidt = rho / (gamma * (pref + p0P)) / dt;
+    dgT = (T)(psidt + sumK * inv_h2);
+}
+
+// Outputs of one cell of the corrector set-up and its partial sums.
+template <typename T>
+__device__ inline void corr_rhs_store(size_t P, size_t N, double b, T dgT, const T (&phf)[3],
+                                      double p0abs, T* __restrict__ phiH, T* __restrict__ rvec,
+                                      T* __restrict__ diag, double* snap_b, double* snap_diag,
+                                      double* snap_p0, double* b64, double (&v)[3]) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) phiH[d * N + P] = phf[d];
     const T bT = (T)b;
     rvec[P] = bT;
     diag[P] = dgT;
@@ -498,9 +496,210 @@ __global__ void __launch_bounds__(kBlock) k_corr_rhs(
     if (snap_b) {
         snap_b[P] = b;
         snap_diag[P] = (double)dgT;
-        snap_p0[P] = (st + mem_)->p_ref + p0P;
+        snap_p0[P] = p0abs;
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_corr_rhs(
+    Phys ph, DevState* st, const T* __restrict__ rn, const T* __restrict__ rk,
+    const T* __restrict__ w, const T* __restrict__ hbya, const T* __restrict__ p0,
+    T* __restrict__ phiH, T* __restrict__ rvec, T* __restrict__ diag, double* part_u,
+    double* snap_b, double* snap_diag, double* snap_p0, double* b64) {
+    MEMBER(ph)
+    const size_t N = ncell(ph);
+    const double dt = (st + mem_)->dt;
+    const double rref = (st + mem_)->rho_ref, pref = (st + mem_)->p_ref;
+    double v[3] = {0.0, 0.0, 0.0};
+    FOR_CELLS(ph)
+    // every load of the cell first, then the FP64 arithmetic
+    T wv[13], rv[13], hl[3][5], pv[7];
+    gather13(w, c, wv);
+    gather13(rk, c, rv);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gather_line(hbya + d * N, c, d, hl[d]);
+    gather7(p0, c, pv);
+    const T rnP = rn[P];
+    loads_issued();
+    double b;
+    T dgT, phf[3];
+    corr_rhs_cell(wv, rv, hl, pv, rnP, dt, rref, pref, ph.gamma, ph.A, ph.inv_V, ph.inv_h,
+                  ph.inv_h2, b, dgT, phf);
+    corr_rhs_store(P, N, b, dgT, phf, pref + (double)pv[0], phiH, rvec, diag, snap_b, snap_diag,
+                   snap_p0, b64, v);
     END_CELLS
+    block_partials<3, 0u>(v, part_u);
+    if (MEMBER_FIRST()) {
+        (st + mem_)->pcg.it_stop = kIterInf;
+        (st + mem_)->pcg.converged = 0;
+        (st + mem_)->pcg.iters = 0;
+    }
+}
+
+// The corrector set-up as a z-march over a 64 x 8 column tile (n a multiple
+// of 64, n >= 128), for the reason of k_mom_sweep_tiled: w, rho_k, the HbyA x
+// and y components and p0 are read once per cell from HBM and their x-y
+// neighbours of the current plane come from halo-2 LDS tiles; the z
+// neighbours of w, rho_k and HbyA_z come from five-plane register queues, of
+// p0 from a three-plane one.  The loads of plane kk + 2 (queue heads at
+// kk + 4, resp. kk + 3) are issued after plane kk's work, a plane ahead of
+// their use, and clamped to the planes the chunk needs.  The per-cell
+// arithmetic is corr_rhs_cell, as in k_corr_rhs.
+template <typename T>
+__global__ void __launch_bounds__(kTX * kTY) k_corr_rhs_tiled(
+    Phys ph, DevState* st, const T* __restrict__ rn, const T* __restrict__ rk,
+    const T* __restrict__ w, const T* __restrict__ hbya, const T* __restrict__ p0,
+    T* __restrict__ phiH, T* __restrict__ rvec, T* __restrict__ diag, double* part_u,
+    double* snap_b, double* snap_diag, double* snap_p0, double* b64) {
+    MEMBER(ph)
+    const size_t N = ncell(ph);
+    const double dt = (st + mem_)->dt;
+    const double rref = (st + mem_)->rho_ref, pref = (st + mem_)->p_ref;
+    const int n = ph.n, cz = ph.cz;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kTX * ty;
+    const int i0 = bp_.x * kTX, j0 = bp_.y * kTY;
+    const int k0 = bz_ * cz;
+    const int k1 = k0 + cz < n ? k0 + cz : n;
+    const size_t nn = (size_t)n * n;
+    constexpr int NF = 5;                       // halo-2 tiles: w, rho_k, HbyA_x, HbyA_y, p0
+    constexpr int kHalo = 4 * kTX + 4 * kTY;    // halo cells of one tile
+    constexpr int kJobs = NF * kHalo;
+    constexpr int kPer = (kJobs + kTX * kTY - 1) / (kTX * kTY);
+    constexpr int kUW = kTX + 4, kUS = (kTY + 4) * kUW;
+    constexpr int kDum = NF * kUS;              // then a scratch slot per thread for idle jobs
+    __shared__ T lds[kDum + kTX * kTY];
+    auto U = [&](int f, int y, int x) -> T& { return lds[f * kUS + y * kUW + x]; };
+    auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
+    const size_t col = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty);
+    typedef const T __attribute__((address_space(1)))* gptr;   // global memory
+    const gptr fsrc[NF] = {(gptr)w, (gptr)rk, (gptr)hbya, (gptr)(hbya + N), (gptr)p0};
+    gptr hsrc[kPer];
+    size_t hoff[kPer];
+    int hdst[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int jb = tid + q * kTX * kTY;
+        hsrc[q] = (gptr)w;
+        hoff[q] = col;
+        hdst[q] = kDum + tid;
+        if (jb < kJobs) {
+            const int f = jb / kHalo, h = jb - f * kHalo;
+            hsrc[q] = fsrc[f];
+            if (h < 4 * kTX) {                  // rows j0-2, j0-1, j0+8, j0+9
+                const int row = h / kTX, x = h - row * kTX;
+                const int yy = row < 2 ? row : kTY + row;
+                hoff[q] = base_ + (size_t)(i0 + x) + (size_t)n * wr(j0 - 2 + yy);
+                hdst[q] = f * kUS + yy * kUW + x + 2;
+            } else {                            // columns i0-2, i0-1, i0+64, i0+65
+                const int t = h - 4 * kTX, c4 = t / kTY, y = t - c4 * kTY;
+                const int xx = c4 < 2 ? c4 : kTX + c4;
+                hoff[q] = base_ + (size_t)wr(i0 - 2 + xx) + (size_t)n * (j0 + y);
+                hdst[q] = f * kUS + (y + 2) * kUW + xx;
+            }
+        }
+    }
+    const T* hz = hbya + 2 * N;
+    // queues (w, rho_k, HbyA_z at kk - 2 .. kk + 2; p0 at kk - 1 .. kk + 1) and
+    // the own values of the first plane
+    T wq[5], rq[5], zq[5], pq[3];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+        wq[t] = w[col + nn * wr(k0 - 2 + t)];
+        rq[t] = rk[col + nn * wr(k0 - 2 + t)];
+        zq[t] = hz[col + nn * wr(k0 - 2 + t)];
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) pq[t] = p0[col + nn * wr(k0 - 1 + t)];
+    T cx = hbya[col + nn * k0], cy = hbya[N + col + nn * k0], cn = rn[col + nn * k0], ch[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) ch[q] = hsrc[q][nn * (size_t)k0 + hoff[q]];
+    T nw, nr, nz, np, nx, ny, nrn, nh[kPer];
+    // queue heads at kq5 (w, rho_k, HbyA_z) and kq3 (p0), own and halo values at kv
+    auto prefetch = [&](int kq5, int kq3, int kv) {
+        const size_t p5 = nn * (size_t)wr(kq5), p3 = nn * (size_t)wr(kq3), pv = nn * (size_t)wr(kv);
+        nw = w[col + p5];
+        nr = rk[col + p5];
+        nz = hz[col + p5];
+        np = p0[col + p3];
+        nx = hbya[col + pv];
+        ny = hbya[N + col + pv];
+        nrn = rn[col + pv];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) nh[q] = hsrc[q][pv + hoff[q]];
+    };
+    auto clampk = [](int a, int hi) { return a < hi ? a : hi; };
+    // last planes the chunk needs: queue heads k1 + 1 (p0: k1), own values k1 - 1
+    prefetch(clampk(k0 + 3, k1 + 1), clampk(k0 + 2, k1), clampk(k0 + 1, k1 - 1));
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int kk = k0; kk < k1; ++kk) {
+        const size_t P = col + nn * (size_t)kk;
+        U(0, ty + 2, tx + 2) = wq[2];
+        U(1, ty + 2, tx + 2) = rq[2];
+        U(2, ty + 2, tx + 2) = cx;
+        U(3, ty + 2, tx + 2) = cy;
+        U(4, ty + 2, tx + 2) = pq[1];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) lds[hdst[q]] = ch[q];
+        lds_barrier();
+        T wv[13], rv[13], hl[3][5], pv[7];
+        auto cross = [&](int f, T c, const T (&zq5)[5], T (&o)[13]) {
+            o[0] = c;
+            o[1] = U(f, ty + 2, tx);
+            o[2] = U(f, ty + 2, tx + 1);
+            o[3] = U(f, ty + 2, tx + 3);
+            o[4] = U(f, ty + 2, tx + 4);
+            o[5] = U(f, ty, tx + 2);
+            o[6] = U(f, ty + 1, tx + 2);
+            o[7] = U(f, ty + 3, tx + 2);
+            o[8] = U(f, ty + 4, tx + 2);
+            o[9] = zq5[0];
+            o[10] = zq5[1];
+            o[11] = zq5[3];
+            o[12] = zq5[4];
+        };
+        cross(0, wq[2], wq, wv);
+        cross(1, rq[2], rq, rv);
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            hl[0][t] = U(2, ty + 2, tx + t);
+            hl[1][t] = U(3, ty + t, tx + 2);
+            hl[2][t] = zq[t];
+        }
+        pv[0] = pq[1];
+        pv[1] = U(4, ty + 2, tx + 1);
+        pv[2] = U(4, ty + 2, tx + 3);
+        pv[3] = U(4, ty + 1, tx + 2);
+        pv[4] = U(4, ty + 3, tx + 2);
+        pv[5] = pq[0];
+        pv[6] = pq[2];
+        lds_barrier();
+        double b;
+        T dgT, phf[3];
+        corr_rhs_cell(wv, rv, hl, pv, cn, dt, rref, pref, ph.gamma, ph.A, ph.inv_V, ph.inv_h,
+                      ph.inv_h2, b, dgT, phf);
+        corr_rhs_store(P, N, b, dgT, phf, pref + (double)pv[0], phiH, rvec, diag, snap_b,
+                       snap_diag, snap_p0, b64, v);
+        // advance the queues with the values loaded one plane ago, then load
+        // the queue heads at kk + 4 (p0: kk + 3) and the values of plane kk + 2
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            wq[t] = wq[t + 1];
+            rq[t] = rq[t + 1];
+            zq[t] = zq[t + 1];
+        }
+        wq[4] = nw;
+        rq[4] = nr;
+        zq[4] = nz;
+        pq[0] = pq[1];
+        pq[1] = pq[2];
+        pq[2] = np;
+        cx = nx;
+        cy = ny;
+        cn = nrn;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) ch[q] = nh[q];
+        prefetch(clampk(kk + 4, k1 + 1), clampk(kk + 3, k1), clampk(kk + 2, k1 - 1));
+    }
     block_partials<3, 0u>(v, part_u);
     if (MEMBER_FIRST()) {
         (st + mem_)->pcg.it_stop = kIterInf;
@@ -1883,12 +2082,21 @@ void Ops<T>::hbya(const Launch& L, const Launch& TL, hipStream_t s, const Phys& 
     }
 }
 template <typename T>
-void Ops<T>::corr_rhs(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, const T* rn,
-                      const T* rk, const T* w, const T* hb, const T* p0, T* phiH, T* r, T* diag,
-                      double* part_u, double* snap_b, double* snap_diag, double* snap_p0,
-                      double* b64) {
+unsigned Ops<T>::corr_rhs(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                          DevState* st, const T* rn, const T* rk, const T* w, const T* hb,
+                          const T* p0, T* phiH, T* r, T* diag, double* part_u, double* snap_b,
+                          double* snap_diag, double* snap_p0, double* b64) {
+    if (TL.nblocks) {
+        Phys pt = ph;
+        pt.cz = TL.cz;
+        pt.nz = TL.nz;
+        LAUNCH(k_corr_rhs_tiled<T>, TL, s, pt, st, rn, rk, w, hb, p0, phiH, r, diag, part_u, snap_b,
+               snap_diag, snap_p0, b64);
+        return TL.nblocks;
+    }
     LAUNCH(k_corr_rhs<T>, L, s, ph, st, rn, rk, w, hb, p0, phiH, r, diag, part_u, snap_b,
            snap_diag, snap_p0, b64);
+    return L.nblocks;
 }
 template <typename T>
 void Ops<T>::refine(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
@@ -1906,15 +2114,15 @@ void Ops<T>::zero(hipStream_t s, T* a, size_t count) {
 template <typename T, bool XUPD>
 static void spmv_launch(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                         DevState* st, int k, const T* r, const T* diag, const T* w, const T* pold,
-                        T* pnew, T* q, T* x, const double* part_u, double* part_s, int fresh,
-                        int maxit, int xzero) {
+                        T* pnew, T* q, T* x, const double* part_u, unsigned nb_u, double* part_s,
+                        int fresh, int maxit, int xzero) {
     if constexpr (sizeof(T) == 4) {
         if (TL.nblocks && TL.v == kRowCells) {
             Phys pt = ph;
             pt.cz = TL.cz;
             pt.nz = TL.nz;
             LAUNCH((k_pcg_spmv_rows<T, kRowCells, XUPD>), TL, s, pt, st, k, r, diag, w, pold, pnew, q,
-                   x, part_u, L.nblocks, part_s, fresh, maxit, xzero);
+                   x, part_u, nb_u, part_s, fresh, maxit, xzero);
             return;
         }
     }
@@ -1923,23 +2131,23 @@ static void spmv_launch(const Launch& L, const Launch& TL, hipStream_t s, const 
         pt.cz = TL.cz;
         pt.nz = TL.nz;
         LAUNCH((k_pcg_spmv_tiled<T, kSpmvRows, XUPD>), TL, s, pt, st, k, r, diag, w, pold, pnew, q,
-               x, part_u, L.nblocks, part_s, fresh, maxit, xzero);
+               x, part_u, nb_u, part_s, fresh, maxit, xzero);
     } else {
         LAUNCH((k_pcg_spmv<T, XUPD>), L, s, ph, st, k, r, diag, w, pold, pnew, q, x, part_u, part_s,
-               L.nblocks, fresh, maxit, xzero);
+               nb_u, fresh, maxit, xzero);
     }
 }
 template <typename T>
 void Ops<T>::pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                       DevState* st, int k, const T* r, const T* diag, const T* w, const T* pold,
-                      T* pnew, T* q, T* x, const double* part_u, double* part_s, int fresh,
-                      int maxit, int xzero) {
+                      T* pnew, T* q, T* x, const double* part_u, unsigned nb_u, double* part_s,
+                      int fresh, int maxit, int xzero) {
     if (k == 0)
-        spmv_launch<T, false>(L, TL, s, ph, st, k, r, diag, w, pold, pnew, q, x, part_u, part_s,
-                              fresh, maxit, xzero);
+        spmv_launch<T, false>(L, TL, s, ph, st, k, r, diag, w, pold, pnew, q, x, part_u, nb_u,
+                              part_s, fresh, maxit, xzero);
     else
-        spmv_launch<T, true>(L, TL, s, ph, st, k, r, diag, w, pold, pnew, q, x, part_u, part_s,
-                             fresh, maxit, xzero);
+        spmv_launch<T, true>(L, TL, s, ph, st, k, r, diag, w, pold, pnew, q, x, part_u, nb_u,
+                             part_s, fresh, maxit, xzero);
 }
 template <typename T>
 void Ops<T>::pcg_update(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,

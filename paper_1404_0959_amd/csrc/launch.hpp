@@ -80,11 +80,13 @@ struct Ops {
     static void hbya(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                      const DevState* st, const T* uin, T* hb, const T* phi, const T* aP,
                      const T* src, const T* rk, T* w, T* p0);
-    // CG starts from x = 0 without x being written (see pcg_spmv's xzero)
-    static void corr_rhs(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
-                         const T* rn, const T* rk, const T* w, const T* hb, const T* p0, T* phiH,
-                         T* r, T* diag, double* part_u, double* snap_b, double* snap_diag,
-                         double* snap_p0, double* b64);
+    // CG starts from x = 0 without x being written (see pcg_spmv's xzero).
+    // TL: the tiled z-march when available.  Returns the number of partials
+    // written to part_u (blocks of the launch used).
+    static unsigned corr_rhs(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                             DevState* st, const T* rn, const T* rk, const T* w, const T* hb,
+                             const T* p0, T* phiH, T* r, T* diag, double* part_u, double* snap_b,
+                             double* snap_diag, double* snap_p0, double* b64);
     // from_zero: x64 is zero and not read (first round of a solve from zero)
     static void refine(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                        const double* x64, const T* d, double* x64n, const double* b64,
@@ -92,10 +94,11 @@ struct Ops {
     static void zero(hipStream_t s, T* a, size_t count);
     // TL: the tiled CG launch of make_spmv_launch (used when TL.nblocks > 0)
     // k >= 1 also applies the previous iteration's x += alpha p; xzero: the
-    // solve started from x = 0 without x being written
+    // solve started from x = 0 without x being written; nb_u: the number of
+    // partials in part_u (blocks of the kernel that wrote them)
     static void pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                          DevState* st, int k, const T* r, const T* diag, const T* w,
-                         const T* pold, T* pnew, T* q, T* x, const double* part_u,
+                         const T* pold, T* pnew, T* q, T* x, const double* part_u, unsigned nb_u,
                          double* part_s, int fresh, int maxit, int xzero);
     static void pcg_update(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                            DevState* st, int k, T* r, const T* q, const T* diag,

@@ -198,6 +198,7 @@ struct pisoc_ctx {
     Phys ph;
     Launch L;
     Launch TL;      // tiled z-marching launch of the field kernels (nblocks = 0: none)
+    unsigned nb_start = 0;   // partials in PS_U of the current solve's start (its set-up kernel)
     Launch TS;      // tiled launch of the CG first half (nblocks = 0: none)
     DevState* st;
     DevState* hst = nullptr;  // pinned host copy (batch entries)
@@ -314,7 +315,7 @@ void set_shape(pisoc_ctx* ctx, const Launch& L) {
 // `pairs` pairs (capture).  Returns the largest iteration count (eager).
 template <typename T>
 pisoc_status run_pcg(pisoc_ctx* ctx, T* r, T* x, T* diag, T* w, T* pp0, T* pp1, T* q, bool fresh,
-                     int pairs, bool eager, int* iters_max, bool xzero) {
+                     int pairs, bool eager, int* iters_max, bool xzero, unsigned nb_first) {
     using O = Ops<T>;
     const int maxit = ctx->prm.p_maxit;
     T* pp[2] = {pp0, pp1};
@@ -323,9 +324,10 @@ pisoc_status run_pcg(pisoc_ctx* ctx, T* r, T* x, T* diag, T* w, T* pp0, T* pp1, 
     auto spmv = [&](int k) {
         // words: r, diag, w read, p, q written; from k = 1 also p_old read and x updated
         timed(ctx, KC_PCG_SPMV, k == 0 ? 5.0 : 8.0, k, [&] {
+            // the start's partials come from the set-up kernel, later ones from k_pcg_update
             O::pcg_spmv(ctx->L, ctx->TS, ctx->stream, ctx->ph, ctx->st, k, r, diag, w,
-                        pp[(k + 1) & 1], pp[k & 1], q, x, pu, ps, fresh ? 1 : 0, maxit,
-                        xzero ? 1 : 0);
+                        pp[(k + 1) & 1], pp[k & 1], q, x, pu, k == 0 ? nb_first : ctx->L.nblocks,
+                        ps, fresh ? 1 : 0, maxit, xzero ? 1 : 0);
         });
     };
     auto update = [&](int k) {
@@ -491,11 +493,15 @@ void enqueue_corr_setup(pisoc_ctx* ctx, StepPtrs<T>& S, int corr, bool guess) {
           [&] { O::hbya(L, ctx->TL, s, ph, ctx->st, ucur, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0); });
     const bool cap = S.snap && corr == 0;
     timed(ctx, KC_CORR_RHS, f32 ? 14 : 12, -1, [&] {
-        O::corr_rhs(L, s, ph, ctx->st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH, S.r, S.dg,
-                    ctx->part(PS_U), cap ? S.snap : nullptr, cap ? S.snap + N : nullptr,
-                    cap ? S.snap + 2 * N : nullptr, S.b64);
+        ctx->nb_start = O::corr_rhs(L, ctx->TL, s, ph, ctx->st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH,
+                                    S.r, S.dg, ctx->part(PS_U), cap ? S.snap : nullptr,
+                                    cap ? S.snap + N : nullptr, cap ? S.snap + 2 * N : nullptr,
+                                    S.b64);
     });
-    if (guess) learned_guess<T>(ctx, S.r, S.x, S.dg, S.w, S.p0, S.pp0, S.q);
+    if (guess) {
+        learned_guess<T>(ctx, S.r, S.x, S.dg, S.w, S.p0, S.pp0, S.q);
+        ctx->nb_start = L.nblocks;   // the guess rewrites the start's partials
+    }
 }
 
 template <typename T>
@@ -572,7 +578,7 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
     int most = 0;
     const int pairs0 = eager ? (ctx->pred_first[corr] > 0 ? ctx->pred_first[corr] : 8) : ctx->caps[corr];
     if ((*err = run_pcg<float>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, true, pairs0, eager,
-                               &most, !guess)) != PISOC_OK)
+                               &most, !guess, ctx->nb_start)) != PISOC_OK)
         return;
     if (eager) ctx->pred_first[corr] = most;
     record_solve(s, ctx->st, B, corr, /*round=*/1, /*add=*/1, /*fin=*/0);
@@ -603,7 +609,7 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
         // the inner correction of this round starts from zero (not written)
         const int pairs = eager ? std::max(2, ctx->pred_later) : ctx->cap_later;
         if ((*err = run_pcg<float>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, false, pairs, eager,
-                                   &most, true)) != PISOC_OK)
+                                   &most, true, ctx->L.nblocks)) != PISOC_OK)
             return;
         if (eager) ctx->pred_later = most;
         record_solve(s, ctx->st, B, corr, round + 1, /*add=*/1, /*fin=*/0);
@@ -679,7 +685,7 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
             const int pairs =
                 eager ? (ctx->pred_first[corr] > 0 ? ctx->pred_first[corr] : 8) : ctx->caps[corr];
             err = run_pcg<T>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, true, pairs, eager, &most,
-                             !guess);
+                             !guess, ctx->nb_start);
             if (eager) ctx->pred_first[corr] = most;
             record_solve(s, ctx->st, ctx->batch, corr, /*round=*/0, /*add=*/1, /*fin=*/1);
         }
@@ -1117,13 +1123,13 @@ void enqueue_probe(pisoc_ctx* ctx) {
     DevState* st = ctx->st;
     O::mom_sweep(L, ctx->TL, s, ph, st, S.un, S.ua, S.phin, S.aP, S.src, S.pn);
     O::hbya(L, ctx->TL, s, ph, st, S.ua, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0);
-    O::corr_rhs(L, s, ph, st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH, S.r, S.dg, ctx->part(PS_U),
-                nullptr, nullptr, nullptr, S.b64);
+    const unsigned nb0 = O::corr_rhs(L, ctx->TL, s, ph, st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH,
+                                     S.r, S.dg, ctx->part(PS_U), nullptr, nullptr, nullptr, S.b64);
     // two CG iterations that cannot stop early (tolerance 0, maxit above 2)
     set_tol(s, st, ctx->batch, 0.0);
     for (int k = 0; k < 2; ++k) {
         O::pcg_spmv(L, ctx->TS, s, ph, st, k, S.r, S.dg, S.w, k ? S.pp0 : S.pp1, k ? S.pp1 : S.pp0,
-                    S.q, S.x, ctx->part(PS_U), ctx->part(PS_S), 1, 1 << 20, 1);
+                    S.q, S.x, ctx->part(PS_U), k ? L.nblocks : nb0, ctx->part(PS_S), 1, 1 << 20, 1);
         O::pcg_update(L, ctx->TS, s, ph, st, k, S.r, S.q, S.dg, ctx->part(PS_S), ctx->part(PS_U));
     }
     if (ctx->prm.n_classes > 0) O::dust_sweep(L, s, ph, st, S.Ya, S.Yb, S.G, S.rj, S.rk);
@@ -1806,7 +1812,7 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
                                 ctx.part(PS_U));
         st = run_pcg<double>(&ctx, r, d_x, dg, const_cast<double*>(d_w), ctx.f<double>(lay.pp0),
                              ctx.f<double>(lay.pp1), ctx.f<double>(lay.q), true, 16, true, nullptr,
-                             false);
+                             false, ctx.L.nblocks);
         if (st == PISOC_OK) {
             const PcgState& g = ctx.hst->pcg;
             if (iters) *iters = g.iters;
