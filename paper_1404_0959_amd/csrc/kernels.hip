@@ -153,6 +153,13 @@ __global__ void __launch_bounds__(kBlock) k_predict(Phys ph, DevState* st, const
 
 // Explicit momentum source s = rho^n u^n / dt + (mu/3) grad(div u^n).
 template <typename T>
+__device__ inline void mom_source_cell(const T (&dv)[13], const T (&uv)[3], T rho, T dt, T m3,
+                                       T inv_h, T (&out)[3]) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) out[m] = rho * uv[m] / dt + m3 * dgauss13(dv, m, inv_h);
+}
+
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_mom_source(Phys ph, const DevState* st,
                                                        const T* __restrict__ rn,
                                                        const T* __restrict__ un,
@@ -169,8 +176,10 @@ __global__ void __launch_bounds__(kBlock) k_mom_source(Phys ph, const DevState* 
     for (int m = 0; m < 3; ++m) uv[m] = un[m * N + P];
     const T rho = (T)(st + mem_)->rho_ref + rn[P];
     loads_issued();
+    T out[3];
+    mom_source_cell(dv, uv, rho, dt, m3, inv_h, out);
 #pragma unroll
-    for (int m = 0; m < 3; ++m) s[m * N + P] = rho * uv[m] / dt + m3 * dgauss13(dv, m, inv_h);
+    for (int m = 0; m < 3; ++m) s[m * N + P] = out[m];
     END_CELLS
 }
 
@@ -715,6 +724,21 @@ __global__ void __launch_bounds__(kTX * kTY) k_corr_rhs_tiled(
 // r.(r/diag), ||r64||^2, ||r64||^2.  FROM_ZERO: x64 is zero (the first round
 // of a solve started from zero) and is not read.  The next inner solve
 // starts from d = 0 without d being written.
+template <typename T>
+__device__ inline void refine_cell(const T (&wv)[13], const double (&xv)[7], const T (&dv)[7],
+                                   double bP, T dgP, double inv_h2, double& xP, double& r) {
+    auto xn = [&](int t) { return xv[t] + (double)dv[t]; };
+    xP = xn(0);
+    double lap = 0.0, sumK = 0.0;
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) {
+        const double kp = i4gr<double>(wv, dd, 0), km = i4gr<double>(wv, dd, -1);
+        lap += kp * (xP - xn(2 + 2 * dd)) + km * (xP - xn(1 + 2 * dd));
+        sumK += kp + km;
+    }
+    r = bP - (((double)dgP - sumK * inv_h2) * xP + lap * inv_h2);
+}
+
 template <typename T, bool FROM_ZERO>
 __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
                                                    const double* __restrict__ x64,
@@ -734,16 +758,8 @@ __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
     const double bP = b64[P];
     const T dgP = diag[P];
     loads_issued();
-    auto xn = [&](int t) { return xv[t] + (double)dv[t]; };
-    const double xP = xn(0);
-    double lap = 0.0, sumK = 0.0;
-#pragma unroll
-    for (int dd = 0; dd < 3; ++dd) {
-        const double kp = i4gr<double>(wv, dd, 0), km = i4gr<double>(wv, dd, -1);
-        lap += kp * (xP - xn(2 + 2 * dd)) + km * (xP - xn(1 + 2 * dd));
-        sumK += kp + km;
-    }
-    const double r = bP - (((double)dgP - sumK * inv_h2) * xP + lap * inv_h2);
+    double xP, r;
+    refine_cell(wv, xv, dv, bP, dgP, inv_h2, xP, r);
     x64n[P] = xP;
     const T rT = (T)r;
     r32[P] = rT;
@@ -1527,6 +1543,18 @@ __global__ void __launch_bounds__(kBlock) k_guess_revert(Phys ph, DevState* st, 
 // ---------------------------------------------------------------- correction
 // p = p0 + p'; corrected face fluxes phi = phiH - K A snGrad(p) on own faces.
 template <typename T>
+__device__ inline void corr_flux_cell(const T (&wv)[13], T p0P, T xP, const T (&p0n)[3],
+                                      const T (&xn)[3], const T (&hP)[3], T A, T inv_h, T& pP,
+                                      T (&fk)[3]) {
+    pP = p0P + xP;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T pQ = p0n[d] + xn[d];
+        fk[d] = hP[d] - i4g(wv, d, 0) * A * (pQ - pP) * inv_h;
+    }
+}
+
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_corr_flux(Phys ph, const T* __restrict__ p0,
                                                       const T* __restrict__ x, const T* __restrict__ w,
                                                       const T* __restrict__ phiH, T* __restrict__ phik,
@@ -1546,13 +1574,11 @@ __global__ void __launch_bounds__(kBlock) k_corr_flux(Phys ph, const T* __restri
         hP[d] = phiH[d * N + P];
     }
     loads_issued();
-    const T pP = p0P + xP;
+    T pP, fk[3];
+    corr_flux_cell(wv, p0P, xP, p0n, xn, hP, A, inv_h, pP, fk);
     pt[P] = pP;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const T pQ = p0n[d] + xn[d];
-        phik[d * N + P] = hP[d] - i4g(wv, d, 0) * A * (pQ - pP) * inv_h;
-    }
+    for (int d = 0; d < 3; ++d) phik[d * N + P] = fk[d];
     if (snap_x) snap_x[P] = (double)xP;
     END_CELLS
 }
@@ -1560,6 +1586,18 @@ __global__ void __launch_bounds__(kBlock) k_corr_flux(Phys ph, const T* __restri
 // Conservative density rho_k = rho^n - dt div(phi) and velocity
 // u = HbyA - grad(p)/a_P.  On the last corrector, partial sums for the mass
 // budget and the divergence checks (sum r, sum |u|^2, max(-rho)).
+template <typename T>
+__device__ inline void corr_update_cell(const T (&pv)[13], const T (&fp)[3], const T (&fm)[3],
+                                        const T (&hb)[3], T rnP, T a, T dt, T inv_V, T inv_h,
+                                        T& r, T (&um)[3]) {
+    T dphi = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dphi += fp[d] - fm[d];
+    r = rnP - dt * dphi * inv_V;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) um[m] = hb[m] - dgauss13(pv, m, inv_h) / a;
+}
+
 template <typename T, bool LAST>
 __global__ void __launch_bounds__(kBlock) k_corr_update(Phys ph, const DevState* st,
                                                         const T* __restrict__ rn,
@@ -1584,17 +1622,14 @@ __global__ void __launch_bounds__(kBlock) k_corr_update(Phys ph, const DevState*
     }
     const T rnP = rn[P], a = aP[P];
     loads_issued();
-    T dphi = T(0);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) dphi += fp[d] - fm[d];
-    const T r = rnP - dt * dphi * inv_V;
+    T r, um[3];
+    corr_update_cell(pv, fp, fm, hb, rnP, a, dt, inv_V, inv_h, r, um);
     rk[P] = r;
     double usq = 0.0;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        const T um = hb[m] - dgauss13(pv, m, inv_h) / a;
-        u[m * N + P] = um;
-        usq += (double)um * (double)um;
+        u[m * N + P] = um[m];
+        usq += (double)um[m] * (double)um[m];
     }
     if (LAST) {
         v[0] += (double)r;
@@ -1608,6 +1643,18 @@ __global__ void __launch_bounds__(kBlock) k_corr_update(Phys ph, const DevState*
 
 // ---------------------------------------------------------------- dust
 // Particle-velocity correction source a = Du/Dt = (u^{n+1} - u^n)/dt + (u^{n+1}.grad)u^{n+1}.
+template <typename T>
+__device__ inline void dudt_cell(const T (&uv)[3][13], const T (&u0)[3], T dt, T inv_h,
+                                 T (&out)[3]) {
+    const T ux = uv[0][0], uy = uv[1][0], uz = uv[2][0];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const T conv = ux * dgauss13(uv[m], 0, inv_h) + uy * dgauss13(uv[m], 1, inv_h) +
+                       uz * dgauss13(uv[m], 2, inv_h);
+        out[m] = (uv[m][0] - u0[m]) / dt + conv;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dudt(Phys ph, const DevState* st,
                                                  const T* __restrict__ un, const T* __restrict__ u1,
@@ -1623,19 +1670,24 @@ __global__ void __launch_bounds__(kBlock) k_dudt(Phys ph, const DevState* st,
         u0[m] = un[m * N + P];
     }
     loads_issued();
-    const T ux = uv[0][0], uy = uv[1][0], uz = uv[2][0];
+    T out[3];
+    dudt_cell(uv, u0, dt, inv_h, out);
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        const T conv = ux * dgauss13(uv[m], 0, inv_h) + uy * dgauss13(uv[m], 1, inv_h) +
-                       uz * dgauss13(uv[m], 2, inv_h);
-        acc[m * N + P] = (uv[m][0] - u0[m]) / dt + conv;
-    }
+    for (int m = 0; m < 3; ++m) acc[m * N + P] = out[m];
     END_CELLS
 }
 
 // Particle mass flux per unit mass ratio on own faces,
 // G_d = phi_d - tau I4(rho^{n+1}) I4(a_d) A  (u_p = u - tau Du/Dt at the face),
 // and the starting mass ratio Y = rho_j^n / rho^n.
+template <typename T>
+__device__ inline void dust_flux_cell(const T (&rv)[13], const T (&al)[3][5], const T (&fv)[3],
+                                      T rj, T rnP, T t, T rref, T A, T (&g)[3], T& y) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[d] = fv[d] - t * (rref + i4g(rv, d, 0)) * i4l<T>(al[d], 0) * A;
+    y = rj / (rref + rnP);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dust_flux(Phys ph, const DevState* st, int cls, const T* __restrict__ phi,
                                                       const T* __restrict__ r1, const T* __restrict__ acc,
@@ -1654,16 +1706,33 @@ __global__ void __launch_bounds__(kBlock) k_dust_flux(Phys ph, const DevState* s
     }
     const T rj = rhoj[P], rnP = rn[P];
     loads_issued();
+    T g[3], y;
+    dust_flux_cell(rv, al, fv, rj, rnP, t, rref, A, g, y);
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-        G[d * N + P] = fv[d] - t * (rref + i4g(rv, d, 0)) * i4l<T>(al[d], 0) * A;
-    Y[P] = rj / (rref + rnP);
+    for (int d = 0; d < 3; ++d) G[d * N + P] = g[d];
+    Y[P] = y;
     END_CELLS
 }
 
 // One Jacobi sweep of the implicit mass-ratio equation
 //   rho^{n+1} Y / dt + (1/V) sum_f G_f^out I4(Y)_f = rho_j^n / dt,
 // diagonal rho^{n+1}/dt + (9/16) div G.
+template <typename T>
+__device__ inline T dust_sweep_cell(const T (&yv)[13], const T (&gpv)[3], const T (&gmv)[3], T rj,
+                                    T r1P, T dt, T inv_V, T rref) {
+    T conv = T(0), dG = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T gp = gpv[d], gm = gmv[d];
+        conv += gp * i4g(yv, d, 0) - gm * i4g(yv, d, -1);
+        dG += gp - gm;
+    }
+    conv *= inv_V;
+    dG *= inv_V;
+    const T off = conv - T(0.5625) * dG * yv[0];
+    return (rj / dt - off) / ((rref + r1P) / dt + T(0.5625) * dG);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dust_sweep(Phys ph, const DevState* st,
                                                        const T* __restrict__ Yin, T* __restrict__ Yout,
@@ -1682,17 +1751,7 @@ __global__ void __launch_bounds__(kBlock) k_dust_sweep(Phys ph, const DevState* 
     }
     const T rj = rhoj[P], r1P = r1[P];
     loads_issued();
-    T conv = T(0), dG = T(0);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const T gp = gpv[d], gm = gmv[d];
-        conv += gp * i4g(yv, d, 0) - gm * i4g(yv, d, -1);
-        dG += gp - gm;
-    }
-    conv *= inv_V;
-    dG *= inv_V;
-    const T off = conv - T(0.5625) * dG * yv[0];
-    Yout[P] = (rj / dt - off) / (((T)(st + mem_)->rho_ref + r1P) / dt + T(0.5625) * dG);
+    Yout[P] = dust_sweep_cell(yv, gpv, gmv, rj, r1P, dt, inv_V, (T)(st + mem_)->rho_ref);
     END_CELLS
 }
 
@@ -1796,13 +1855,13 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(const double* part, uns
 // and the dust class masses from the partials of the last corrector and of
 // the dust finish.
 __global__ void __launch_bounds__(kBlock) k_step_finish(Phys ph, DevState* st,
-                                                        const double* part_mass,
+                                                        const double* part_mass, unsigned nb_mass,
                                                         const double* part_dust, int ncls,
                                                         unsigned nbt, size_t cls_stride) {
     const int m = blockIdx.x;
     DevState* sm = st + m;
     double v[3];
-    reduce_member<3, 4u>(part_mass, nbt, ph.batch, m, v);
+    reduce_member<3, 4u>(part_mass, nb_mass, ph.batch, m, v);
     if (flat_tid() == 0) {
         sm->mass_gas = (sm->rho_ref * (double)ph.N + v[0]) * ph.V;
         sm->usq = v[1];
@@ -1946,6 +2005,450 @@ Launch make_launch_shaped(int n, int batch, int bx, int cz) {
     return L;
 }
 
+// ---------------------------------------------------------------- tiled
+// Generic z-march over 64 x 8 column tiles (n a multiple of 64, n >= 128) for
+// the field kernels whose cells gather 13-point crosses, for the reason of
+// k_mom_sweep_tiled: each of the K::NS stencil fields is read once per cell
+// from HBM; its x-y neighbours on the current plane come from a halo-2 LDS
+// tile, its z neighbours from a five-plane register queue.  With K::FACES the
+// three components of a face field and the low-side neighbour each needs
+// (x - 1, y - 1, z - 1) come from LDS and a two-plane queue.  K supplies the
+// cell's own point values (K::load, issued a plane ahead) and the arithmetic
+// (K::cell: the cell function of the gathered kernel, fed the same gathered
+// arrays, lines and 7-point crosses being subsets of the 13-point one).
+// Loads past the chunk's last needed plane are clamped to planes already read.
+template <typename T, class K>
+__global__ void __launch_bounds__(kTX * kTY) k_tiled(Phys ph, DevState* st, K kern) {
+    MEMBER(ph)
+    constexpr int NS = K::NS;
+    constexpr bool FACES = K::FACES;
+    constexpr int NRA = K::NR > 0 ? K::NR : 1;
+    const size_t N = ncell(ph);
+    K k = kern;
+    k.member(ph, st + mem_);
+    const int n = ph.n, cz = ph.cz;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kTX * ty;
+    const int i0 = bp_.x * kTX, j0 = bp_.y * kTY;
+    const int k0 = bz_ * cz;
+    const int k1 = k0 + cz < n ? k0 + cz : n;
+    const size_t nn = (size_t)n * n;
+    constexpr int kHalo = 4 * kTX + 4 * kTY;    // halo cells of one stencil tile
+    constexpr int kJobs = NS * kHalo + (FACES ? kTY + kTX : 0);
+    constexpr int kPer = (kJobs + kTX * kTY - 1) / (kTX * kTY);
+    constexpr int kUW = kTX + 4, kUS = (kTY + 4) * kUW;
+    constexpr int kFX = NS * kUS;
+    constexpr int kFY = kFX + (FACES ? kTY * (kTX + 1) : 0);
+    constexpr int kDum = kFY + (FACES ? (kTY + 1) * kTX : 0);
+    // one LDS array: the stencil tiles, face x at x = i0 - 1 .. i0 + 63, face
+    // y at y = j0 - 1 .. j0 + 7, a scratch slot per thread for idle halo jobs
+    __shared__ T lds[kDum + kTX * kTY];
+    auto U = [&](int f, int y, int x) -> T& { return lds[f * kUS + y * kUW + x]; };
+    auto FX = [&](int y, int x) -> T& { return lds[kFX + y * (kTX + 1) + x]; };
+    auto FY = [&](int y, int x) -> T& { return lds[kFY + y * kTX + x]; };
+    auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
+    auto clampk = [](int a, int hi) { return a < hi ? a : hi; };
+    const size_t col = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty);
+    typedef const T __attribute__((address_space(1)))* gptr;   // global memory
+    gptr hsrc[kPer];
+    size_t hoff[kPer];
+    int hdst[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int jb = tid + q * kTX * kTY;
+        hsrc[q] = (gptr)k.sf[0];
+        hoff[q] = col;
+        hdst[q] = kDum + tid;
+        if (jb < NS * kHalo) {
+            const int f = jb / kHalo, h = jb - f * kHalo;
+#pragma unroll
+            for (int g = 0; g < NS; ++g)    // a select, not a dynamic index into k.sf
+                if (g == f) hsrc[q] = (gptr)k.sf[g];
+            if (h < 4 * kTX) {                  // rows j0-2, j0-1, j0+8, j0+9
+                const int row = h / kTX, x = h - row * kTX;
+                const int yy = row < 2 ? row : kTY + row;
+                hoff[q] = base_ + (size_t)(i0 + x) + (size_t)n * wr(j0 - 2 + yy);
+                hdst[q] = f * kUS + yy * kUW + x + 2;
+            } else {                            // columns i0-2, i0-1, i0+64, i0+65
+                const int t = h - 4 * kTX, c4 = t / kTY, y = t - c4 * kTY;
+                const int xx = c4 < 2 ? c4 : kTX + c4;
+                hoff[q] = base_ + (size_t)wr(i0 - 2 + xx) + (size_t)n * (j0 + y);
+                hdst[q] = f * kUS + (y + 2) * kUW + xx;
+            }
+        } else if (FACES && jb < NS * kHalo + kTY) {   // face x at x = i0 - 1
+            const int y = jb - NS * kHalo;
+            hsrc[q] = (gptr)k.face;
+            hoff[q] = base_ + (size_t)wr(i0 - 1) + (size_t)n * (j0 + y);
+            hdst[q] = kFX + y * (kTX + 1);
+        } else if (FACES && jb < kJobs) {               // face y at y = j0 - 1
+            const int x = jb - NS * kHalo - kTY;
+            hsrc[q] = (gptr)(k.face + N);
+            hoff[q] = base_ + (size_t)(i0 + x) + (size_t)n * wr(j0 - 1);
+            hdst[q] = kFY + x;
+        }
+    }
+    T q5[NS][5], fzq[2] = {T(0), T(0)}, cfx = T(0), cfy = T(0), ch[kPer];
+#pragma unroll
+    for (int f = 0; f < NS; ++f)
+#pragma unroll
+        for (int t = 0; t < 5; ++t) q5[f][t] = k.sf[f][col + nn * wr(k0 - 2 + t)];
+    if (FACES) {
+        fzq[0] = k.face[2 * N + col + nn * wr(k0 - 1)];
+        fzq[1] = k.face[2 * N + col + nn * k0];
+        cfx = k.face[col + nn * k0];
+        cfy = k.face[N + col + nn * k0];
+    }
+    typename K::Pts cur = k.load(col + nn * k0), nxt;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) ch[q] = hsrc[q][nn * (size_t)k0 + hoff[q]];
+    T nq[NS], nfz = T(0), nfx = T(0), nfy = T(0), nh[kPer];
+    auto prefetch = [&](int kq, int kv) {       // queue heads at plane kq, values at kv
+        const size_t p5 = nn * (size_t)wr(kq), pv = nn * (size_t)wr(kv);
+#pragma unroll
+        for (int f = 0; f < NS; ++f) nq[f] = k.sf[f][col + p5];
+        if (FACES) {
+            nfz = k.face[2 * N + col + pv];
+            nfx = k.face[col + pv];
+            nfy = k.face[N + col + pv];
+        }
+        nxt = k.load(col + pv);
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) nh[q] = hsrc[q][pv + hoff[q]];
+    };
+    // last planes the chunk needs: queue heads k1 + 1, values k1 - 1
+    prefetch(clampk(k0 + 3, k1 + 1), clampk(k0 + 1, k1 - 1));
+    double acc[NRA];
+    k.init(acc);
+    for (int kk = k0; kk < k1; ++kk) {
+        const size_t P = col + nn * (size_t)kk;
+#pragma unroll
+        for (int f = 0; f < NS; ++f) U(f, ty + 2, tx + 2) = q5[f][2];
+        if (FACES) {
+            FX(ty, tx + 1) = cfx;
+            FY(ty + 1, tx) = cfy;
+        }
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) lds[hdst[q]] = ch[q];
+        lds_barrier();
+        T v[NS][13], fp[3], fm[3];
+#pragma unroll
+        for (int f = 0; f < NS; ++f) {
+            v[f][0] = q5[f][2];
+            v[f][1] = U(f, ty + 2, tx);
+            v[f][2] = U(f, ty + 2, tx + 1);
+            v[f][3] = U(f, ty + 2, tx + 3);
+            v[f][4] = U(f, ty + 2, tx + 4);
+            v[f][5] = U(f, ty, tx + 2);
+            v[f][6] = U(f, ty + 1, tx + 2);
+            v[f][7] = U(f, ty + 3, tx + 2);
+            v[f][8] = U(f, ty + 4, tx + 2);
+            v[f][9] = q5[f][0];
+            v[f][10] = q5[f][1];
+            v[f][11] = q5[f][3];
+            v[f][12] = q5[f][4];
+        }
+        if (FACES) {
+            fp[0] = FX(ty, tx + 1);
+            fm[0] = FX(ty, tx);
+            fp[1] = FY(ty + 1, tx);
+            fm[1] = FY(ty, tx);
+            fp[2] = fzq[1];
+            fm[2] = fzq[0];
+        }
+        lds_barrier();
+        k.cell(P, v, fp, fm, cur, acc);
+        // advance the queues with the values loaded a plane ago, then load the
+        // queue heads at kk + 4 and the values of plane kk + 2
+#pragma unroll
+        for (int f = 0; f < NS; ++f) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) q5[f][t] = q5[f][t + 1];
+            q5[f][4] = nq[f];
+        }
+        if (FACES) {
+            fzq[0] = fzq[1];
+            fzq[1] = nfz;
+            cfx = nfx;
+            cfy = nfy;
+        }
+        cur = nxt;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) ch[q] = nh[q];
+        prefetch(clampk(kk + 4, k1 + 1), clampk(kk + 2, k1 - 1));
+    }
+    if constexpr (K::NR > 0) block_partials<K::NR, K::MASK>(acc, k.part);
+    if (MEMBER_FIRST()) k.first(st + mem_);
+}
+
+// The 13-point cross v of a field: the line of five cells along d (as
+// gather_line) and the 7-point cross (as gather7).
+template <typename T>
+__device__ inline void cross_line(const T (&v)[13], int d, T (&o)[5]) {
+    o[0] = v[1 + 4 * d];
+    o[1] = v[2 + 4 * d];
+    o[2] = v[0];
+    o[3] = v[3 + 4 * d];
+    o[4] = v[4 + 4 * d];
+}
+template <typename T, typename R>
+__device__ inline void cross7(const T (&v)[13], R (&o)[7]) {
+    o[0] = (R)v[0];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        o[1 + 2 * d] = (R)v[2 + 4 * d];
+        o[2 + 2 * d] = (R)v[3 + 4 * d];
+    }
+}
+
+// Cell functors of k_tiled.  Members: NS stencil fields sf, FACES and the face
+// field, NR partial sums (block_partials mask MASK) into part, the member's
+// constants (member), the point values (Pts, load), the arithmetic (cell),
+// and what the member's first thread does at the end (first).
+template <typename T>
+struct TiledBase {
+    static constexpr bool FACES = false;
+    static constexpr int NR = 0;
+    static constexpr unsigned MASK = 0u;
+    const T* face = nullptr;
+    double* part = nullptr;
+    size_t NT = 0;
+    __device__ void init(double* acc) const { acc[0] = 0.0; }
+    __device__ void first(DevState*) const {}
+};
+
+template <typename T>
+struct TiledMomSource : TiledBase<T> {
+    static constexpr int NS = 1;          // div u
+    const T* sf[1];
+    const T *rn, *un;
+    T* src;
+    T dt, m3, inv_h, rref;
+    struct Pts { T rn, u[3]; };
+    __device__ void member(const Phys& ph, const DevState* d) {
+        this->NT = ph.NT;
+        dt = (T)d->dt;
+        m3 = (T)(ph.mu / 3.0);
+        inv_h = (T)ph.inv_h;
+        rref = (T)d->rho_ref;
+    }
+    __device__ Pts load(size_t P) const {
+        return {rn[P], {un[P], un[this->NT + P], un[2 * this->NT + P]}};
+    }
+    __device__ void cell(size_t P, const T (&v)[1][13], const T (&)[3], const T (&)[3],
+                         const Pts& p, double*) const {
+        T out[3];
+        mom_source_cell(v[0], p.u, rref + p.rn, dt, m3, inv_h, out);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) src[m * this->NT + P] = out[m];
+    }
+};
+
+template <typename T>
+struct TiledCorrFlux : TiledBase<T> {
+    static constexpr int NS = 3;          // w, p0, x
+    const T* sf[3];
+    const T* phiH;
+    T *phik, *pt;
+    double* snap_x;
+    T A, inv_h;
+    struct Pts { T h[3]; };
+    __device__ void member(const Phys& ph, const DevState*) {
+        this->NT = ph.NT;
+        A = (T)ph.A;
+        inv_h = (T)ph.inv_h;
+    }
+    __device__ Pts load(size_t P) const {
+        return {{phiH[P], phiH[this->NT + P], phiH[2 * this->NT + P]}};
+    }
+    __device__ void cell(size_t P, const T (&v)[3][13], const T (&)[3], const T (&)[3],
+                         const Pts& p, double*) const {
+        T p0n[3], xn[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            p0n[d] = v[1][3 + 4 * d];   // +1 along d
+            xn[d] = v[2][3 + 4 * d];
+        }
+        T pP, fk[3];
+        corr_flux_cell(v[0], v[1][0], v[2][0], p0n, xn, p.h, A, inv_h, pP, fk);
+        pt[P] = pP;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) phik[d * this->NT + P] = fk[d];
+        if (snap_x) snap_x[P] = (double)v[2][0];
+    }
+};
+
+template <typename T, bool LAST>
+struct TiledCorrUpdate : TiledBase<T> {
+    static constexpr int NS = 1;          // p
+    static constexpr bool FACES = true;   // phi_k
+    static constexpr int NR = LAST ? 3 : 0;
+    static constexpr unsigned MASK = 4u;  // column 2 is a maximum
+    const T* sf[1];
+    const T *rn, *hbya, *aP;
+    T *rk, *u;
+    T dt, inv_V, inv_h;
+    double rref;
+    struct Pts { T hb[3], rn, a; };
+    __device__ void member(const Phys& ph, const DevState* d) {
+        this->NT = ph.NT;
+        dt = (T)d->dt;
+        inv_V = (T)ph.inv_V;
+        inv_h = (T)ph.inv_h;
+        rref = d->rho_ref;
+    }
+    __device__ void init(double* acc) const {
+        acc[0] = 0.0;
+        if (LAST) {
+            acc[1] = 0.0;
+            acc[2] = -__builtin_inf();
+        }
+    }
+    __device__ Pts load(size_t P) const {
+        return {{hbya[P], hbya[this->NT + P], hbya[2 * this->NT + P]}, rn[P], aP[P]};
+    }
+    __device__ void cell(size_t P, const T (&v)[1][13], const T (&fp)[3], const T (&fm)[3],
+                         const Pts& p, double* acc) const {
+        T r, um[3];
+        corr_update_cell(v[0], fp, fm, p.hb, p.rn, p.a, dt, inv_V, inv_h, r, um);
+        rk[P] = r;
+        double usq = 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            u[m * this->NT + P] = um[m];
+            usq += (double)um[m] * (double)um[m];
+        }
+        if (LAST) {
+            acc[0] += (double)r;
+            acc[1] += usq;
+            const double nrho = -(rref + (double)r);
+            acc[2] = nrho > acc[2] ? nrho : acc[2];
+        }
+    }
+};
+
+template <typename T>
+struct TiledRefineFromZero : TiledBase<T> {
+    static constexpr int NS = 2;          // w, d
+    static constexpr int NR = 3;
+    const T* sf[2];
+    const double* b64;
+    const T* diag;
+    double* x64n;
+    T* r32;
+    double inv_h2;
+    struct Pts { double b; T dg; };
+    __device__ void member(const Phys& ph, const DevState*) { inv_h2 = ph.inv_h2; }
+    __device__ void init(double* acc) const { acc[0] = acc[1] = acc[2] = 0.0; }
+    __device__ Pts load(size_t P) const { return {b64[P], diag[P]}; }
+    __device__ void cell(size_t P, const T (&v)[2][13], const T (&)[3], const T (&)[3],
+                         const Pts& p, double* acc) const {
+        const double xv[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        T dv[7];
+        cross7(v[1], dv);
+        double xP, r;
+        refine_cell(v[0], xv, dv, p.b, p.dg, inv_h2, xP, r);
+        x64n[P] = xP;
+        const T rT = (T)r;
+        r32[P] = rT;
+        acc[0] += (double)rT * ((double)rT / (double)p.dg);
+        acc[1] += r * r;
+        acc[2] += r * r;
+    }
+    __device__ void first(DevState* d) const {
+        d->pcg.it_stop = kIterInf;
+        d->pcg.converged = 0;
+        d->pcg.iters = 0;
+    }
+};
+
+template <typename T>
+struct TiledDudt : TiledBase<T> {
+    static constexpr int NS = 3;          // u^{n+1}
+    const T* sf[3];
+    const T* un;
+    T* acc_out;
+    T dt, inv_h;
+    struct Pts { T u0[3]; };
+    __device__ void member(const Phys& ph, const DevState* d) {
+        this->NT = ph.NT;
+        dt = (T)d->dt;
+        inv_h = (T)ph.inv_h;
+    }
+    __device__ Pts load(size_t P) const {
+        return {{un[P], un[this->NT + P], un[2 * this->NT + P]}};
+    }
+    __device__ void cell(size_t P, const T (&v)[3][13], const T (&)[3], const T (&)[3],
+                         const Pts& p, double*) const {
+        T out[3];
+        dudt_cell(v, p.u0, dt, inv_h, out);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) acc_out[m * this->NT + P] = out[m];
+    }
+};
+
+template <typename T>
+struct TiledDustFlux : TiledBase<T> {
+    static constexpr int NS = 4;          // rho^{n+1}, a_x, a_y, a_z
+    const T* sf[4];
+    const T *phi, *rhoj, *rn;
+    T *G, *Y;
+    T A, t, rref;
+    int cls;
+    struct Pts { T f[3], rj, rn; };
+    __device__ void member(const Phys& ph, const DevState* d) {
+        this->NT = ph.NT;
+        A = (T)ph.A;
+        t = (T)d->tau[cls];
+        rref = (T)d->rho_ref;
+    }
+    __device__ Pts load(size_t P) const {
+        return {{phi[P], phi[this->NT + P], phi[2 * this->NT + P]}, rhoj[P], rn[P]};
+    }
+    __device__ void cell(size_t P, const T (&v)[4][13], const T (&)[3], const T (&)[3],
+                         const Pts& p, double*) const {
+        T al[3][5];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cross_line(v[1 + d], d, al[d]);
+        T g[3], y;
+        dust_flux_cell(v[0], al, p.f, p.rj, p.rn, t, rref, A, g, y);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) G[d * this->NT + P] = g[d];
+        Y[P] = y;
+    }
+};
+
+template <typename T>
+struct TiledDustSweep : TiledBase<T> {
+    static constexpr int NS = 1;          // Y_in
+    static constexpr bool FACES = true;   // G
+    const T* sf[1];
+    const T *rhoj, *r1;
+    T* Yout;
+    T dt, inv_V, rref;
+    struct Pts { T rj, r1; };
+    __device__ void member(const Phys& ph, const DevState* d) {
+        dt = (T)d->dt;
+        inv_V = (T)ph.inv_V;
+        rref = (T)d->rho_ref;
+    }
+    __device__ Pts load(size_t P) const { return {rhoj[P], r1[P]}; }
+    __device__ void cell(size_t P, const T (&v)[1][13], const T (&fp)[3], const T (&fm)[3],
+                         const Pts& p, double*) const {
+        Yout[P] = dust_sweep_cell(v[0], fp, fm, p.rj, p.r1, dt, inv_V, rref);
+    }
+};
+
+// Launch of k_tiled over the tiled launch TL; returns its block count (the
+// number of partials a reducing functor writes).
+template <typename T, class K>
+static unsigned tiled_launch(const Launch& TL, hipStream_t s, const Phys& ph, const DevState* st,
+                             const K& k) {
+    Phys pt = ph;
+    pt.cz = TL.cz;
+    pt.nz = TL.nz;
+    hipLaunchKernelGGL((k_tiled<T, K>), TL.grid, TL.block, 0, s, pt, const_cast<DevState*>(st), k);
+    return TL.nblocks;
+}
+
 Launch make_launch(int n, int batch) {
     const int bx = n >= 64 ? 64 : 32;
     const int gx = (n + bx - 1) / bx, gy = (n + kBlock / bx - 1) / (kBlock / bx);
@@ -2047,8 +2550,17 @@ void Ops<T>::predict(const Launch& L, hipStream_t s, const Phys& ph, DevState* s
            phi, rs, aP, divu, pn);
 }
 template <typename T>
-void Ops<T>::mom_source(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                        const T* rn, const T* un, const T* divu, T* src) {
+void Ops<T>::mom_source(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                        const DevState* st, const T* rn, const T* un, const T* divu, T* src) {
+    if (TL.nblocks) {
+        TiledMomSource<T> k{};
+        k.sf[0] = divu;
+        k.rn = rn;
+        k.un = un;
+        k.src = src;
+        tiled_launch<T>(TL, s, ph, st, k);
+        return;
+    }
     LAUNCH(k_mom_source<T>, L, s, ph, st, rn, un, divu, src);
 }
 template <typename T>
@@ -2099,13 +2611,26 @@ unsigned Ops<T>::corr_rhs(const Launch& L, const Launch& TL, hipStream_t s, cons
     return L.nblocks;
 }
 template <typename T>
-void Ops<T>::refine(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
-                    const double* x64, const T* d, double* x64n, const double* b64, const T* w,
-                    const T* diag, T* r32, double* part_u, bool from_zero) {
+unsigned Ops<T>::refine(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                        DevState* st, const double* x64, const T* d, double* x64n,
+                        const double* b64, const T* w, const T* diag, T* r32, double* part_u,
+                        bool from_zero) {
+    if (from_zero && TL.nblocks) {
+        TiledRefineFromZero<T> k{};
+        k.sf[0] = w;
+        k.sf[1] = d;
+        k.part = part_u;
+        k.b64 = b64;
+        k.diag = diag;
+        k.x64n = x64n;
+        k.r32 = r32;
+        return tiled_launch<T>(TL, s, ph, st, k);
+    }
     if (from_zero)
         LAUNCH((k_refine<T, true>), L, s, ph, st, x64, d, x64n, b64, w, diag, r32, part_u);
     else
         LAUNCH((k_refine<T, false>), L, s, ph, st, x64, d, x64n, b64, w, diag, r32, part_u);
+    return L.nblocks;
 }
 template <typename T>
 void Ops<T>::zero(hipStream_t s, T* a, size_t count) {
@@ -2170,33 +2695,99 @@ void Ops<T>::helm_start(const Launch& L, hipStream_t s, const Phys& ph, DevState
     LAUNCH(k_helm_start<T>, L, s, ph, st, psidt, w, b, x, r, diag, part_u);
 }
 template <typename T>
-void Ops<T>::corr_flux(const Launch& L, hipStream_t s, const Phys& ph, const T* p0, const T* x,
-                       const T* w, const T* phiH, T* phik, T* pt, double* snap_x) {
+void Ops<T>::corr_flux(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                       const DevState* st, const T* p0, const T* x, const T* w, const T* phiH,
+                       T* phik, T* pt, double* snap_x) {
+    if (TL.nblocks) {
+        TiledCorrFlux<T> k{};
+        k.sf[0] = w;
+        k.sf[1] = p0;
+        k.sf[2] = x;
+        k.phiH = phiH;
+        k.phik = phik;
+        k.pt = pt;
+        k.snap_x = snap_x;
+        tiled_launch<T>(TL, s, ph, st, k);
+        return;
+    }
     LAUNCH(k_corr_flux<T>, L, s, ph, p0, x, w, phiH, phik, pt, snap_x);
 }
+template <typename T, bool LAST>
+static unsigned corr_update_tiled(const Launch& TL, hipStream_t s, const Phys& ph,
+                                  const DevState* st, const T* rn, const T* phik, const T* hb,
+                                  const T* pt, const T* aP, T* rk, T* u, double* part_mass) {
+    TiledCorrUpdate<T, LAST> k{};
+    k.sf[0] = pt;
+    k.face = phik;
+    k.part = part_mass;
+    k.rn = rn;
+    k.hbya = hb;
+    k.aP = aP;
+    k.rk = rk;
+    k.u = u;
+    return tiled_launch<T>(TL, s, ph, st, k);
+}
 template <typename T>
-void Ops<T>::corr_update(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                         bool last, const T* rn, const T* phik, const T* hb, const T* pt,
-                         const T* aP, T* rk, T* u, double* part_mass) {
+unsigned Ops<T>::corr_update(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                             const DevState* st, bool last, const T* rn, const T* phik,
+                             const T* hb, const T* pt, const T* aP, T* rk, T* u,
+                             double* part_mass) {
+    if (TL.nblocks)
+        return last ? corr_update_tiled<T, true>(TL, s, ph, st, rn, phik, hb, pt, aP, rk, u, part_mass)
+                    : corr_update_tiled<T, false>(TL, s, ph, st, rn, phik, hb, pt, aP, rk, u,
+                                                  part_mass);
     if (last)
         LAUNCH((k_corr_update<T, true>), L, s, ph, st, rn, phik, hb, pt, aP, rk, u, part_mass);
     else
         LAUNCH((k_corr_update<T, false>), L, s, ph, st, rn, phik, hb, pt, aP, rk, u, part_mass);
+    return L.nblocks;
 }
 template <typename T>
-void Ops<T>::dudt(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st, const T* un,
-                  const T* u1, T* acc) {
+void Ops<T>::dudt(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                  const DevState* st, const T* un, const T* u1, T* acc) {
+    if (TL.nblocks) {
+        TiledDudt<T> k{};
+        for (int m = 0; m < 3; ++m) k.sf[m] = u1 + (size_t)m * ph.NT;
+        k.un = un;
+        k.acc_out = acc;
+        tiled_launch<T>(TL, s, ph, st, k);
+        return;
+    }
     LAUNCH(k_dudt<T>, L, s, ph, st, un, u1, acc);
 }
 template <typename T>
-void Ops<T>::dust_flux(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st, int cls,
-                       const T* phi, const T* r1, const T* acc, T* G, const T* rhoj, const T* rn,
-                       T* Y) {
+void Ops<T>::dust_flux(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                       const DevState* st, int cls, const T* phi, const T* r1, const T* acc, T* G,
+                       const T* rhoj, const T* rn, T* Y) {
+    if (TL.nblocks) {
+        TiledDustFlux<T> k{};
+        k.sf[0] = r1;
+        for (int d = 0; d < 3; ++d) k.sf[1 + d] = acc + (size_t)d * ph.NT;
+        k.phi = phi;
+        k.rhoj = rhoj;
+        k.rn = rn;
+        k.G = G;
+        k.Y = Y;
+        k.cls = cls;
+        tiled_launch<T>(TL, s, ph, st, k);
+        return;
+    }
     LAUNCH(k_dust_flux<T>, L, s, ph, st, cls, phi, r1, acc, G, rhoj, rn, Y);
 }
 template <typename T>
-void Ops<T>::dust_sweep(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                        const T* Yin, T* Yout, const T* G, const T* rhoj, const T* r1) {
+void Ops<T>::dust_sweep(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                        const DevState* st, const T* Yin, T* Yout, const T* G, const T* rhoj,
+                        const T* r1) {
+    if (TL.nblocks) {
+        TiledDustSweep<T> k{};
+        k.sf[0] = Yin;
+        k.face = G;
+        k.rhoj = rhoj;
+        k.r1 = r1;
+        k.Yout = Yout;
+        tiled_launch<T>(TL, s, ph, st, k);
+        return;
+    }
     LAUNCH(k_dust_sweep<T>, L, s, ph, st, Yin, Yout, G, rhoj, r1);
 }
 template <typename T>
@@ -2228,9 +2819,10 @@ void sum_partials(hipStream_t s, const double* part, unsigned nb, double* dst) {
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64, 4), 0, s, part, nb, dst);
 }
 void step_finish(hipStream_t s, const Phys& ph, DevState* st, const double* part_mass,
-                 const double* part_dust, int ncls, unsigned nbt, size_t cls_stride) {
+                 unsigned nb_mass, const double* part_dust, int ncls, unsigned nbt,
+                 size_t cls_stride) {
     hipLaunchKernelGGL(k_step_finish, dim3(ph.batch), dim3(64, 4), 0, s, ph, st, part_mass,
-                       part_dust, ncls, nbt, cls_stride);
+                       nb_mass, part_dust, ncls, nbt, cls_stride);
 }
 void commit(hipStream_t s, DevState* st, int batch) {
     hipLaunchKernelGGL(k_commit, dim3((batch + 63) / 64), dim3(64), 0, s, st, batch);

@@ -71,8 +71,10 @@ struct Ops {
                         const double* part_cfl, double dt_fixed, double cfl, double growth,
                         double dt_max, const T* rn, const T* un, const T* phi, T* rs, T* aP,
                         T* divu, T* pn);
-    static void mom_source(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                           const T* rn, const T* un, const T* divu, T* src);
+    // Field kernels taking TL run as k_tiled z-marches when TL.nblocks > 0;
+    // those that write partials return how many (blocks of the launch used).
+    static void mom_source(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                           const DevState* st, const T* rn, const T* un, const T* divu, T* src);
     // TL: tiled launch (used when TL.nblocks > 0)
     static void mom_sweep(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                           const DevState* st, const T* uin, T* uout, const T* phi, const T* aP,
@@ -88,9 +90,10 @@ struct Ops {
                              const T* p0, T* phiH, T* r, T* diag, double* part_u, double* snap_b,
                              double* snap_diag, double* snap_p0, double* b64);
     // from_zero: x64 is zero and not read (first round of a solve from zero)
-    static void refine(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
-                       const double* x64, const T* d, double* x64n, const double* b64,
-                       const T* w, const T* diag, T* r32, double* part_u, bool from_zero);
+    static unsigned refine(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                           DevState* st, const double* x64, const T* d, double* x64n,
+                           const double* b64, const T* w, const T* diag, T* r32,
+                           double* part_u, bool from_zero);
     static void zero(hipStream_t s, T* a, size_t count);
     // TL: the tiled CG launch of make_spmv_launch (used when TL.nblocks > 0)
     // k >= 1 also applies the previous iteration's x += alpha p; xzero: the
@@ -108,18 +111,21 @@ struct Ops {
     static void helm_start(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                            const T* psidt, const T* w, const T* b, const T* x, T* r, T* diag,
                            double* part_u);
-    static void corr_flux(const Launch& L, hipStream_t s, const Phys& ph, const T* p0, const T* x,
-                          const T* w, const T* phiH, T* phik, T* pt, double* snap_x);
-    static void corr_update(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                            bool last, const T* rn, const T* phik, const T* hb, const T* pt,
-                            const T* aP, T* rk, T* u, double* part_mass);
-    static void dudt(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                     const T* un, const T* u1, T* acc);
-    static void dust_flux(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                          int cls, const T* phi, const T* r1, const T* acc, T* G, const T* rhoj,
-                          const T* rn, T* Y);
-    static void dust_sweep(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                           const T* Yin, T* Yout, const T* G, const T* rhoj, const T* r1);
+    static void corr_flux(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                          const DevState* st, const T* p0, const T* x, const T* w,
+                          const T* phiH, T* phik, T* pt, double* snap_x);
+    static unsigned corr_update(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                                const DevState* st, bool last, const T* rn, const T* phik,
+                                const T* hb, const T* pt, const T* aP, T* rk, T* u,
+                                double* part_mass);
+    static void dudt(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                     const DevState* st, const T* un, const T* u1, T* acc);
+    static void dust_flux(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                          const DevState* st, int cls, const T* phi, const T* r1, const T* acc,
+                          T* G, const T* rhoj, const T* rn, T* Y);
+    static void dust_sweep(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                           const DevState* st, const T* Yin, T* Yout, const T* G,
+                           const T* rhoj, const T* r1);
     static void dust_faceflux(const Launch& L, hipStream_t s, const Phys& ph, const T* Y, T* G);
     static void dust_finish(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                             const T* rhoj, const T* F, T* rhoj1, double* part);
@@ -153,8 +159,10 @@ void finalize_sums(hipStream_t s, const double* part, unsigned nbt, int batch, i
 // Total of nb partials (one column) into dst[0].
 void sum_partials(hipStream_t s, const double* part, unsigned nb, double* dst);
 // Per member: end-of-step mass budget and flags.
+// nb_mass: partials of the last corrector update; nbt: of the dust finish
 void step_finish(hipStream_t s, const Phys& ph, DevState* st, const double* part_mass,
-                 const double* part_dust, int ncls, unsigned nbt, size_t cls_stride);
+                 unsigned nb_mass, const double* part_dust, int ncls, unsigned nbt,
+                 size_t cls_stride);
 // Per member: t += dt, dt_prev = dt (the step is accepted); fold the step
 // record into the accumulators.
 void commit(hipStream_t s, DevState* st, int batch);

@@ -199,6 +199,7 @@ struct pisoc_ctx {
     Launch L;
     Launch TL;      // tiled z-marching launch of the field kernels (nblocks = 0: none)
     unsigned nb_start = 0;   // partials in PS_U of the current solve's start (its set-up kernel)
+    unsigned nb_mass = 0;    // partials in PS_MASS (the last corrector update)
     Launch TS;      // tiled launch of the CG first half (nblocks = 0: none)
     DevState* st;
     DevState* hst = nullptr;  // pinned host copy (batch entries)
@@ -467,7 +468,8 @@ void enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S) {
         O::predict(L, s, ph, st, ctx->part(PS_CFL), p.dt_fixed, p.cfl, p.dt_growth, p.dt_max, S.rn,
                    S.un, S.phin, S.rk, S.aP, S.divu, S.pn);
     });
-    timed(ctx, KC_MOM_SOURCE, 8, -1, [&] { O::mom_source(L, s, ph, st, S.rn, S.un, S.divu, S.src); });
+    timed(ctx, KC_MOM_SOURCE, 8, -1,
+          [&] { O::mom_source(L, ctx->TL, s, ph, st, S.rn, S.un, S.divu, S.src); });
     T* uin = S.un;
     for (int i = 0; i < p.n_mom_sweeps; ++i) {
         T* uout = (i & 1) ? S.ub : S.ua;
@@ -514,11 +516,12 @@ void enqueue_corr_finish(pisoc_ctx* ctx, StepPtrs<T>& S, int corr) {
     const bool cap = S.snap && corr == 0;
     T* ucur = ucur_of(ctx, S);
     timed(ctx, KC_CORR_FLUX, 10, -1, [&] {
-        O::corr_flux(L, s, ph, S.p0, S.x, S.w, S.phiH, S.phik, S.q, cap ? S.snap + 3 * N : nullptr);
+        O::corr_flux(L, ctx->TL, s, ph, ctx->st, S.p0, S.x, S.w, S.phiH, S.phik, S.q,
+                     cap ? S.snap + 3 * N : nullptr);
     });
     timed(ctx, KC_CORR_UPDATE, 13, -1, [&] {
-        O::corr_update(L, s, ph, ctx->st, corr == ctx->prm.n_corr - 1, S.rn, S.phik, S.hb, S.q, S.aP,
-                       S.rk, ucur, ctx->part(PS_MASS));
+        ctx->nb_mass = O::corr_update(L, ctx->TL, s, ph, ctx->st, corr == ctx->prm.n_corr - 1, S.rn,
+                                      S.phik, S.hb, S.q, S.aP, S.rk, ucur, ctx->part(PS_MASS));
     });
 }
 
@@ -533,16 +536,17 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
     const size_t N = ctx->NT();
     T* ucur = ucur_of(ctx, S);
     if (p.n_classes > 0) {
-        timed(ctx, KC_DUDT, 9, -1, [&] { O::dudt(L, s, ph, st, S.un, ucur, S.acc); });
+        timed(ctx, KC_DUDT, 9, -1, [&] { O::dudt(L, ctx->TL, s, ph, st, S.un, ucur, S.acc); });
         for (int c = 0; c < p.n_classes; ++c) {
             timed(ctx, KC_DUST_FLUX, 13, -1, [&] {
-                O::dust_flux(L, s, ph, st, c, S.phik, S.rk, S.acc, S.G, S.rj + c * N, S.rn, S.Ya);
+                O::dust_flux(L, ctx->TL, s, ph, st, c, S.phik, S.rk, S.acc, S.G, S.rj + c * N, S.rn,
+                             S.Ya);
             });
             T* yin = S.Ya;
             T* yout = S.Yb;
             for (int i = 0; i < p.n_dust_sweeps; ++i) {
                 timed(ctx, KC_DUST_SWEEP, 7, -1,
-                      [&] { O::dust_sweep(L, s, ph, st, yin, yout, S.G, S.rj + c * N, S.rk); });
+                      [&] { O::dust_sweep(L, ctx->TL, s, ph, st, yin, yout, S.G, S.rj + c * N, S.rk); });
                 std::swap(yin, yout);
             }
             timed(ctx, KC_DUST_FACEFLUX, 7, -1, [&] { O::dust_faceflux(L, s, ph, yin, S.G); });
@@ -551,8 +555,8 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
             });
         }
     }
-    step_finish(s, ph, st, ctx->part(PS_MASS), ctx->part(PS_DUST), p.n_classes, L.nblocks,
-                ctx->lay.max_blocks);
+    step_finish(s, ph, st, ctx->part(PS_MASS), ctx->nb_mass, ctx->part(PS_DUST), p.n_classes,
+                L.nblocks, ctx->lay.max_blocks);
 }
 
 // FP32 storage: mixed-precision iterative refinement of M p' = b for every
@@ -584,16 +588,17 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
     record_solve(s, ctx->st, B, corr, /*round=*/1, /*add=*/1, /*fin=*/0);
     const int max_rounds = eager ? p.max_refine : ctx->rounds;
     int round = 0;
+    unsigned nb_ref = ctx->L.nblocks;   // partials of the last refinement
     for (;;) {
         const bool from_zero = round == 0 && !guess;
         timed(ctx, KC_REFINE, from_zero ? 8 : 10, -1, [&] {
-            Ops<float>::refine(ctx->L, s, ctx->ph, ctx->st, xa, S.x, xb, S.b64, S.w, S.dg, S.r,
-                               ctx->part(PS_U), from_zero);
+            nb_ref = Ops<float>::refine(ctx->L, ctx->TL, s, ctx->ph, ctx->st, xa, S.x, xb, S.b64,
+                                        S.w, S.dg, S.r, ctx->part(PS_U), from_zero);
         });
         std::swap(xa, xb);
         ++round;
-        // column 1 (||r64||^2) of the 3 columns written with L.nblocks blocks
-        finalize_sums(s, ctx->part(PS_U) + ctx->L.nblocks, ctx->L.nblocks, B, 1, ctx->st, 0);
+        // column 1 (||r64||^2) of the 3 columns written with nb_ref blocks
+        finalize_sums(s, ctx->part(PS_U) + nb_ref, nb_ref, B, 1, ctx->st, 0);
         if (round >= max_rounds) break;
         if (eager) {
             if ((*err = sync_state(ctx)) != PISOC_OK) return;
@@ -609,7 +614,7 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
         // the inner correction of this round starts from zero (not written)
         const int pairs = eager ? std::max(2, ctx->pred_later) : ctx->cap_later;
         if ((*err = run_pcg<float>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, false, pairs, eager,
-                                   &most, true, ctx->L.nblocks)) != PISOC_OK)
+                                   &most, true, nb_ref)) != PISOC_OK)
             return;
         if (eager) ctx->pred_later = most;
         record_solve(s, ctx->st, B, corr, round + 1, /*add=*/1, /*fin=*/0);
@@ -1132,7 +1137,7 @@ void enqueue_probe(pisoc_ctx* ctx) {
                     S.q, S.x, ctx->part(PS_U), k ? L.nblocks : nb0, ctx->part(PS_S), 1, 1 << 20, 1);
         O::pcg_update(L, ctx->TS, s, ph, st, k, S.r, S.q, S.dg, ctx->part(PS_S), ctx->part(PS_U));
     }
-    if (ctx->prm.n_classes > 0) O::dust_sweep(L, s, ph, st, S.Ya, S.Yb, S.G, S.rj, S.rk);
+    if (ctx->prm.n_classes > 0) O::dust_sweep(L, ctx->TL, s, ph, st, S.Ya, S.Yb, S.G, S.rj, S.rk);
 }
 
 pisoc_status tune_ctx(pisoc_ctx* ctx, const char* cache_path, int force, int* bx_out, int* cz_out) {
