@@ -169,6 +169,42 @@ def test_step_parity_hit128_tiled(P, ora):
     compare_state(P, ora, s, o)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tiled_kernels_match_gathered(P, monkeypatch, precision):
+    """At 128^3 the stencil kernels run as tiled z-marches (the generic k_tiled
+    driver, the tiled corrector set-up, momentum sweep and CG first half); with
+    PISOC_UNTILED=1 the same step runs the gathered kernels. Both call the same
+    cell arithmetic; only reduction order differs, so the CG iteration counts
+    agree and the fields agree to rounding (FP64: 1e-11 of the spread; FP32:
+    the bound of the FP32 tests, 5e-5 of the spread plus 16 FP32 ulps of the
+    magnitude -- a dust density of 1e-3 with a spread of 1e-5 after two steps
+    differs by a few ulps of its stored value)."""
+    case = make_hit_case(128, 7, mach=0.5, stokes=(0.1, 0.4))
+    kw = dict(p_tol=1e-9) if precision == "fp64" else dict(
+        p_tol=1e-6, precision=P.FP32_REFINED, inner_tol=1e-6)
+    runs = []
+    for untiled in (False, True):
+        if untiled:
+            monkeypatch.setenv("PISOC_UNTILED", "1")
+        s = P.Solver.from_case(case, **kw)
+        st, info = s.step(2)
+        assert st == 0
+        runs.append((gpu_fields(P, s), [i["pcg_iters"] for i in info],
+                     [i["mass_gas"] for i in info]))
+        monkeypatch.delenv("PISOC_UNTILED", raising=False)
+    (fa, ia, ma), (fb, ib, mb) = runs
+    assert ia == ib
+    mass_tol = 1e-12 if precision == "fp64" else 1e-10   # FP32: sums of FP32-stored densities
+    for a, b in zip(ma, mb):
+        assert abs(a - b) <= mass_tol * abs(a)
+    tol, ulps = (1e-11, 0.0) if precision == "fp64" else (5e-5, 16 * np.finfo(np.float32).eps)
+    for k in fa:
+        spread = np.max(np.abs(fb[k] - fb[k].mean()))
+        bound = tol * spread + ulps * np.max(np.abs(fb[k]))
+        d = np.max(np.abs(fa[k] - fb[k]))
+        assert d <= bound, (k, d, bound)
+
+
 def test_step_parity_hit256_bench_workload(P, ora):
     """One step of the 256^3 workload the benchmark times (decaying HIT, Mach
     0.2, one class at Stokes 0.2, residual 1e-6), in its launch configuration:
