@@ -2015,8 +2015,11 @@ Launch make_launch_shaped(int n, int batch, int bx, int cz) {
 // (x - 1, y - 1, z - 1) come from LDS and a two-plane queue.  K supplies the
 // cell's own point values (K::load, issued a plane ahead) and the arithmetic
 // (K::cell: the cell function of the gathered kernel, fed the same gathered
-// arrays, lines and 7-point crosses being subsets of the 13-point one).
-// Loads past the chunk's last needed plane are clamped to planes already read.
+// arrays, lines and 7-point crosses being subsets of the 13-point one).  A
+// halo value is loaded together with its owner tile's queue head of the same
+// plane (four planes ahead, then held in a three-plane register queue), so
+// that the two reads of a line fall together in L2.  Loads past the chunk's
+// last needed plane are clamped to planes already read.
 template <typename T, class K>
 __global__ void __launch_bounds__(kTX * kTY) k_tiled(Phys ph, DevState* st, K kern) {
     MEMBER(ph)
@@ -2086,7 +2089,8 @@ __global__ void __launch_bounds__(kTX * kTY) k_tiled(Phys ph, DevState* st, K ke
             hdst[q] = kFY + x;
         }
     }
-    T q5[NS][5], fzq[2] = {T(0), T(0)}, cfx = T(0), cfy = T(0), ch[kPer];
+    // halo values of planes kk .. kk + 2 (hq[.][0] goes to LDS at plane kk)
+    T q5[NS][5], fzq[2] = {T(0), T(0)}, cfx = T(0), cfy = T(0), hq[kPer][3];
 #pragma unroll
     for (int f = 0; f < NS; ++f)
 #pragma unroll
@@ -2099,10 +2103,14 @@ __global__ void __launch_bounds__(kTX * kTY) k_tiled(Phys ph, DevState* st, K ke
     }
     typename K::Pts cur = k.load(col + nn * k0), nxt;
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) ch[q] = hsrc[q][nn * (size_t)k0 + hoff[q]];
+    for (int q = 0; q < kPer; ++q)
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+            hq[q][t] = hsrc[q][nn * (size_t)wr(clampk(k0 + t, k1 - 1)) + hoff[q]];
     T nq[NS], nfz = T(0), nfx = T(0), nfy = T(0), nh[kPer];
-    auto prefetch = [&](int kq, int kv) {       // queue heads at plane kq, values at kv
-        const size_t p5 = nn * (size_t)wr(kq), pv = nn * (size_t)wr(kv);
+    // queue heads at plane kq, halo values at kh, own values at kv
+    auto prefetch = [&](int kq, int kh, int kv) {
+        const size_t p5 = nn * (size_t)wr(kq), phh = nn * (size_t)wr(kh), pv = nn * (size_t)wr(kv);
 #pragma unroll
         for (int f = 0; f < NS; ++f) nq[f] = k.sf[f][col + p5];
         if (FACES) {
@@ -2112,10 +2120,10 @@ __global__ void __launch_bounds__(kTX * kTY) k_tiled(Phys ph, DevState* st, K ke
         }
         nxt = k.load(col + pv);
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) nh[q] = hsrc[q][pv + hoff[q]];
+        for (int q = 0; q < kPer; ++q) nh[q] = hsrc[q][phh + hoff[q]];
     };
-    // last planes the chunk needs: queue heads k1 + 1, values k1 - 1
-    prefetch(clampk(k0 + 3, k1 + 1), clampk(k0 + 1, k1 - 1));
+    // last planes the chunk needs: queue heads k1 + 1, halo and own values k1 - 1
+    prefetch(clampk(k0 + 3, k1 + 1), clampk(k0 + 3, k1 - 1), clampk(k0 + 1, k1 - 1));
     double acc[NRA];
     k.init(acc);
     for (int kk = k0; kk < k1; ++kk) {
@@ -2127,7 +2135,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_tiled(Phys ph, DevState* st, K ke
             FY(ty + 1, tx) = cfy;
         }
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) lds[hdst[q]] = ch[q];
+        for (int q = 0; q < kPer; ++q) lds[hdst[q]] = hq[q][0];
         lds_barrier();
         T v[NS][13], fp[3], fm[3];
 #pragma unroll
@@ -2172,8 +2180,12 @@ __global__ void __launch_bounds__(kTX * kTY) k_tiled(Phys ph, DevState* st, K ke
         }
         cur = nxt;
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) ch[q] = nh[q];
-        prefetch(clampk(kk + 4, k1 + 1), clampk(kk + 2, k1 - 1));
+        for (int q = 0; q < kPer; ++q) {
+            hq[q][0] = hq[q][1];
+            hq[q][1] = hq[q][2];
+            hq[q][2] = nh[q];
+        }
+        prefetch(clampk(kk + 4, k1 + 1), clampk(kk + 4, k1 - 1), clampk(kk + 2, k1 - 1));
     }
     if constexpr (K::NR > 0) block_partials<K::NR, K::MASK>(acc, k.part);
     if (MEMBER_FIRST()) k.first(st + mem_);
