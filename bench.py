@@ -88,7 +88,10 @@ def cpu_baseline(case, p_tol, target_s):
 
 
 def timed_run(P, torch, case, prec, args, guess=None):
-    """Warm up, then time exactly args.steps steps with per-kernel events on."""
+    """Warm up, time exactly args.steps steps (the value), then as many more with
+    per-kernel HIP events on the library's stream (the per-kernel times of the
+    roofline: recording an event pair around every launch adds a gap before
+    each kernel, so those steps are not the ones the value is taken from)."""
     kw = dict(p_tol=args.p_tol, cfl=0.5, n_corr=2, n_mom_sweeps=4, n_dust_sweeps=4)
     if guess is not None:
         kw.update(guess=P.GUESS_LEARNED, guess_weights=guess.data_ptr(),
@@ -96,16 +99,20 @@ def timed_run(P, torch, case, prec, args, guess=None):
     s = P.Solver.from_case(case, precision=prec, inner_tol=args.inner_tol, **kw)
     st, _ = s.step(args.warmup)
     torch.cuda.synchronize()
-    s.profile(True)
-    torch.cuda.synchronize()
     t_start = time.perf_counter()
     st, info = s.step(args.steps)
     torch.cuda.synchronize()
     t_end = time.perf_counter()
+    s.profile(True)
+    torch.cuda.synchronize()
+    t_prof = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    t_prof_end = time.perf_counter()
     prof = s.profile_read()
     s.profile(False)
     s.close()
-    return t_end - t_start, info, prof
+    return t_end - t_start, info, prof, t_prof_end - t_prof
 
 
 def ensemble_run(P, torch, args, weights):
@@ -269,14 +276,16 @@ def main():
     modes = ["fp64", "fp32", "fp32_learned"] if args.mode == "all" else [args.mode]
     for m in modes:
         prec = P.FP64 if m == "fp64" else P.FP32_REFINED
-        el, info, prof = timed_run(P, torch, case, prec, args,
-                                   guess=weights if m == "fp32_learned" else None)
+        el, info, prof, el_prof = timed_run(P, torch, case, prec, args,
+                                            guess=weights if m == "fp32_learned" else None)
         iters = [i["pcg_iters"] for i in info]
-        runs[m] = dict(elapsed=el, info=info, prof=prof, value=n3 * args.steps / el,
+        runs[m] = dict(elapsed=el, elapsed_events=el_prof, info=info, prof=prof,
+                       value=n3 * args.steps / el,
                        iters=float(np.mean([sum(i) / len(i) for i in iters])),
                        guess_steps=sum(1 for i in info if not i["flags"] & P.FLAG_GUESS_SKIPPED))
         log(f"{m}: {el * 1e3 / args.steps:.3f} ms/step, {n3 * args.steps / el:.4e} cell-steps/s, "
-            f"mean CG iterations per solve {runs[m]['iters']:.2f}")
+            f"mean CG iterations per solve {runs[m]['iters']:.2f} "
+            f"({el_prof * 1e3 / args.steps:.3f} ms/step with per-kernel events)")
     head = modes[-1]
     H = runs[head]
     roof, kernels = roofline(H["prof"])
@@ -317,6 +326,7 @@ def main():
         "cpu_baseline": cpu,
         "pcg_iters_mean": H["iters"],
         "modes": {m: {"value": r["value"], "ms_per_step": r["elapsed"] * 1e3 / args.steps,
+                      "ms_per_step_with_kernel_events": r["elapsed_events"] * 1e3 / args.steps,
                       "pcg_iters_mean": r["iters"], "steps_with_guess": r["guess_steps"]
                       if m == "fp32_learned" else 0} for m, r in runs.items()},
         "kernels": kernels,
