@@ -1857,7 +1857,7 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(const double* part, uns
 __global__ void __launch_bounds__(kBlock) k_step_finish(Phys ph, DevState* st,
                                                         const double* part_mass, unsigned nb_mass,
                                                         const double* part_dust, int ncls,
-                                                        unsigned nbt, size_t cls_stride) {
+                                                        unsigned nb_dust, size_t cls_stride) {
     const int m = blockIdx.x;
     DevState* sm = st + m;
     double v[3];
@@ -1871,7 +1871,7 @@ __global__ void __launch_bounds__(kBlock) k_step_finish(Phys ph, DevState* st,
     }
     for (int c = 0; c < ncls; ++c) {
         double mm[1];
-        reduce_member<1, 0u>(part_dust + (size_t)c * cls_stride, nbt, ph.batch, m, mm);
+        reduce_member<1, 0u>(part_dust + (size_t)c * cls_stride, nb_dust, ph.batch, m, mm);
         if (flat_tid() == 0) sm->mass_p[c] = mm[0] * ph.V;
     }
 }
@@ -2449,6 +2449,37 @@ struct TiledDustSweep : TiledBase<T> {
     }
 };
 
+// The face dust fluxes and the conservative finish in one pass: F_f =
+// G_f I4(Y)_f on the cell's own faces and, from the low-side G and the same
+// four Y cells, on its lower faces (the values k_dust_faceflux would store
+// in the neighbours), then rho_j^{n+1} = rho_j^n - dt div(F) and the partial
+// mass sum, as k_dust_finish.  F itself is not stored.
+template <typename T>
+struct TiledDustFinish : TiledBase<T> {
+    static constexpr int NS = 1;          // Y
+    static constexpr bool FACES = true;   // G
+    static constexpr int NR = 1;
+    const T* sf[1];
+    const T* rhoj;
+    T* rhoj1;
+    T dt, inv_V;
+    struct Pts { T rj; };
+    __device__ void member(const Phys& ph, const DevState* d) {
+        dt = (T)d->dt;
+        inv_V = (T)ph.inv_V;
+    }
+    __device__ Pts load(size_t P) const { return {rhoj[P]}; }
+    __device__ void cell(size_t P, const T (&v)[1][13], const T (&fp)[3], const T (&fm)[3],
+                         const Pts& p, double* acc) const {
+        T dF = T(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dF += fp[d] * i4g(v[0], d, 0) - fm[d] * i4g(v[0], d, -1);
+        const T out = p.rj - dt * dF * inv_V;
+        rhoj1[P] = out;
+        acc[0] += (double)out;
+    }
+};
+
 // Launch of k_tiled over the tiled launch TL; returns its block count (the
 // number of partials a reducing functor writes).
 template <typename T, class K>
@@ -2812,6 +2843,18 @@ void Ops<T>::dust_finish(const Launch& L, hipStream_t s, const Phys& ph, const D
     LAUNCH(k_dust_finish<T>, L, s, ph, st, rhoj, F, rhoj1, part);
 }
 template <typename T>
+unsigned Ops<T>::dust_finish_fused(const Launch& TL, hipStream_t s, const Phys& ph,
+                                   const DevState* st, const T* Y, const T* G, const T* rhoj,
+                                   T* rhoj1, double* part) {
+    TiledDustFinish<T> k{};
+    k.sf[0] = Y;
+    k.face = G;
+    k.part = part;
+    k.rhoj = rhoj;
+    k.rhoj1 = rhoj1;
+    return tiled_launch<T>(TL, s, ph, st, k);
+}
+template <typename T>
 void Ops<T>::stats_gas(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                        const T* r, const T* u, double* part) {
     LAUNCH(k_stats_gas<T>, L, s, ph, st, r, u, part);
@@ -2831,10 +2874,10 @@ void sum_partials(hipStream_t s, const double* part, unsigned nb, double* dst) {
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64, 4), 0, s, part, nb, dst);
 }
 void step_finish(hipStream_t s, const Phys& ph, DevState* st, const double* part_mass,
-                 unsigned nb_mass, const double* part_dust, int ncls, unsigned nbt,
+                 unsigned nb_mass, const double* part_dust, int ncls, unsigned nb_dust,
                  size_t cls_stride) {
     hipLaunchKernelGGL(k_step_finish, dim3(ph.batch), dim3(64, 4), 0, s, ph, st, part_mass,
-                       nb_mass, part_dust, ncls, nbt, cls_stride);
+                       nb_mass, part_dust, ncls, nb_dust, cls_stride);
 }
 void commit(hipStream_t s, DevState* st, int batch) {
     hipLaunchKernelGGL(k_commit, dim3((batch + 63) / 64), dim3(64), 0, s, st, batch);

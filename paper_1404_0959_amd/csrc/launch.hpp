@@ -129,6 +129,11 @@ struct Ops {
     static void dust_faceflux(const Launch& L, hipStream_t s, const Phys& ph, const T* Y, T* G);
     static void dust_finish(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                             const T* rhoj, const T* F, T* rhoj1, double* part);
+    // dust_faceflux and dust_finish in one tiled pass (TL.nblocks > 0), F not
+    // stored; returns the number of partials written
+    static unsigned dust_finish_fused(const Launch& TL, hipStream_t s, const Phys& ph,
+                                      const DevState* st, const T* Y, const T* G,
+                                      const T* rhoj, T* rhoj1, double* part);
     static void stats_gas(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                           const T* r, const T* u, double* part);
     // st non-null: per-member (a, b) = st[m].aff
@@ -159,9 +164,9 @@ void finalize_sums(hipStream_t s, const double* part, unsigned nbt, int batch, i
 // Total of nb partials (one column) into dst[0].
 void sum_partials(hipStream_t s, const double* part, unsigned nb, double* dst);
 // Per member: end-of-step mass budget and flags.
-// nb_mass: partials of the last corrector update; nbt: of the dust finish
+// nb_mass: partials of the last corrector update; nb_dust: of the dust finish
 void step_finish(hipStream_t s, const Phys& ph, DevState* st, const double* part_mass,
-                 unsigned nb_mass, const double* part_dust, int ncls, unsigned nbt,
+                 unsigned nb_mass, const double* part_dust, int ncls, unsigned nb_dust,
                  size_t cls_stride);
 // Per member: t += dt, dt_prev = dt (the step is accepted); fold the step
 // record into the accumulators.

@@ -529,6 +529,7 @@ template <typename T>
 void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
     using O = Ops<T>;
     const pisoc_params& p = ctx->prm;
+    unsigned nb_dust = ctx->L.nblocks;   // partials of the dust finish
     const Phys& ph = ctx->ph;
     const Launch& L = ctx->L;
     hipStream_t s = ctx->stream;
@@ -549,14 +550,23 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
                       [&] { O::dust_sweep(L, ctx->TL, s, ph, st, yin, yout, S.G, S.rj + c * N, S.rk); });
                 std::swap(yin, yout);
             }
-            timed(ctx, KC_DUST_FACEFLUX, 7, -1, [&] { O::dust_faceflux(L, s, ph, yin, S.G); });
-            timed(ctx, KC_DUST_FINISH, 5, -1, [&] {
-                O::dust_finish(L, s, ph, st, S.rj + c * N, S.G, S.rj1 + c * N, ctx->part(PS_DUST + c));
-            });
+            if (ctx->TL.nblocks) {
+                // face fluxes and finish in one tiled pass (words: Y, G, rho_j read, rho_j' written)
+                timed(ctx, KC_DUST_FINISH, 6, -1, [&] {
+                    nb_dust = O::dust_finish_fused(ctx->TL, s, ph, st, yin, S.G, S.rj + c * N,
+                                                   S.rj1 + c * N, ctx->part(PS_DUST + c));
+                });
+            } else {
+                timed(ctx, KC_DUST_FACEFLUX, 7, -1, [&] { O::dust_faceflux(L, s, ph, yin, S.G); });
+                timed(ctx, KC_DUST_FINISH, 5, -1, [&] {
+                    O::dust_finish(L, s, ph, st, S.rj + c * N, S.G, S.rj1 + c * N,
+                                   ctx->part(PS_DUST + c));
+                });
+            }
         }
     }
     step_finish(s, ph, st, ctx->part(PS_MASS), ctx->nb_mass, ctx->part(PS_DUST), p.n_classes,
-                L.nblocks, ctx->lay.max_blocks);
+                nb_dust, ctx->lay.max_blocks);
 }
 
 // FP32 storage: mixed-precision iterative refinement of M p' = b for every
