@@ -2480,6 +2480,74 @@ struct TiledDustFinish : TiledBase<T> {
     }
 };
 
+// The corrector's flux correction and update in one pass: p = p0 + p' on the
+// 13-point cross, the corrected fluxes phi = phiH - K A snGrad(p) on the
+// cell's own faces (stored) and on its lower faces (from the low-side phiH
+// and the same w and p cells: bitwise the values the neighbours store), then
+// the update of rho_k and u as k_corr_update.  p itself is not stored.
+template <typename T, bool LAST>
+struct TiledCorrFluxUpdate : TiledBase<T> {
+    static constexpr int NS = 3;          // w, p0, p'
+    static constexpr bool FACES = true;   // phiH
+    static constexpr int NR = LAST ? 3 : 0;
+    static constexpr unsigned MASK = 4u;
+    const T* sf[3];
+    const T *rn, *hbya, *aP;
+    T *phik, *rk, *u;
+    double* snap_x;
+    T A, inv_h, dt, inv_V;
+    double rref;
+    struct Pts { T hb[3], rn, a; };
+    __device__ void member(const Phys& ph, const DevState* d) {
+        this->NT = ph.NT;
+        A = (T)ph.A;
+        inv_h = (T)ph.inv_h;
+        dt = (T)d->dt;
+        inv_V = (T)ph.inv_V;
+        rref = d->rho_ref;
+    }
+    __device__ void init(double* acc) const {
+        acc[0] = 0.0;
+        if (LAST) {
+            acc[1] = 0.0;
+            acc[2] = -__builtin_inf();
+        }
+    }
+    __device__ Pts load(size_t P) const {
+        return {{hbya[P], hbya[this->NT + P], hbya[2 * this->NT + P]}, rn[P], aP[P]};
+    }
+    __device__ void cell(size_t P, const T (&v)[3][13], const T (&hp)[3], const T (&hm)[3],
+                         const Pts& p, double* acc) const {
+        T pv[13];
+#pragma unroll
+        for (int t = 0; t < 13; ++t) pv[t] = v[1][t] + v[2][t];
+        const T pP = pv[0];
+        T fp[3], fm[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            fp[d] = hp[d] - i4g(v[0], d, 0) * A * (pv[3 + 4 * d] - pP) * inv_h;
+            fm[d] = hm[d] - i4g(v[0], d, -1) * A * (pP - pv[2 + 4 * d]) * inv_h;
+            phik[d * this->NT + P] = fp[d];
+        }
+        if (snap_x) snap_x[P] = (double)v[2][0];
+        T r, um[3];
+        corr_update_cell(pv, fp, fm, p.hb, p.rn, p.a, dt, inv_V, inv_h, r, um);
+        rk[P] = r;
+        double usq = 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            u[m * this->NT + P] = um[m];
+            usq += (double)um[m] * (double)um[m];
+        }
+        if (LAST) {
+            acc[0] += (double)r;
+            acc[1] += usq;
+            const double nrho = -(rref + (double)r);
+            acc[2] = nrho > acc[2] ? nrho : acc[2];
+        }
+    }
+};
+
 // Launch of k_tiled over the tiled launch TL; returns its block count (the
 // number of partials a reducing functor writes).
 template <typename T, class K>
@@ -2841,6 +2909,37 @@ template <typename T>
 void Ops<T>::dust_finish(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                          const T* rhoj, const T* F, T* rhoj1, double* part) {
     LAUNCH(k_dust_finish<T>, L, s, ph, st, rhoj, F, rhoj1, part);
+}
+template <typename T, bool LAST>
+static unsigned corr_finish_tiled(const Launch& TL, hipStream_t s, const Phys& ph,
+                                  const DevState* st, const T* p0, const T* x, const T* w,
+                                  const T* phiH, T* phik, double* snap_x, const T* rn,
+                                  const T* hb, const T* aP, T* rk, T* u, double* part_mass) {
+    TiledCorrFluxUpdate<T, LAST> k{};
+    k.sf[0] = w;
+    k.sf[1] = p0;
+    k.sf[2] = x;
+    k.face = phiH;
+    k.part = part_mass;
+    k.rn = rn;
+    k.hbya = hb;
+    k.aP = aP;
+    k.phik = phik;
+    k.rk = rk;
+    k.u = u;
+    k.snap_x = snap_x;
+    return tiled_launch<T>(TL, s, ph, st, k);
+}
+template <typename T>
+unsigned Ops<T>::corr_finish_fused(const Launch& TL, hipStream_t s, const Phys& ph,
+                                   const DevState* st, bool last, const T* p0, const T* x,
+                                   const T* w, const T* phiH, T* phik, double* snap_x,
+                                   const T* rn, const T* hb, const T* aP, T* rk, T* u,
+                                   double* part_mass) {
+    return last ? corr_finish_tiled<T, true>(TL, s, ph, st, p0, x, w, phiH, phik, snap_x, rn, hb,
+                                             aP, rk, u, part_mass)
+                : corr_finish_tiled<T, false>(TL, s, ph, st, p0, x, w, phiH, phik, snap_x, rn, hb,
+                                              aP, rk, u, part_mass);
 }
 template <typename T>
 unsigned Ops<T>::dust_finish_fused(const Launch& TL, hipStream_t s, const Phys& ph,

@@ -114,6 +114,13 @@ struct Ops {
     static void corr_flux(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                           const DevState* st, const T* p0, const T* x, const T* w,
                           const T* phiH, T* phik, T* pt, double* snap_x);
+    // corr_flux and corr_update in one tiled pass (TL.nblocks > 0), p not
+    // stored; returns the number of mass partials written (last corrector)
+    static unsigned corr_finish_fused(const Launch& TL, hipStream_t s, const Phys& ph,
+                                      const DevState* st, bool last, const T* p0, const T* x,
+                                      const T* w, const T* phiH, T* phik, double* snap_x,
+                                      const T* rn, const T* hb, const T* aP, T* rk, T* u,
+                                      double* part_mass);
     static unsigned corr_update(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                                 const DevState* st, bool last, const T* rn, const T* phik,
                                 const T* hb, const T* pt, const T* aP, T* rk, T* u,

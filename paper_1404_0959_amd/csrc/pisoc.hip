@@ -515,13 +515,24 @@ void enqueue_corr_finish(pisoc_ctx* ctx, StepPtrs<T>& S, int corr) {
     const size_t N = ctx->NT();
     const bool cap = S.snap && corr == 0;
     T* ucur = ucur_of(ctx, S);
+    const bool last = corr == ctx->prm.n_corr - 1;
+    if (ctx->TL.nblocks) {
+        // flux correction and update in one tiled pass (words: w, p0, p', phiH x3,
+        // HbyA x3, rho^n, a_P read; phi x3, rho_k, u x3 written)
+        timed(ctx, KC_CORR_UPDATE, 18, -1, [&] {
+            ctx->nb_mass = O::corr_finish_fused(ctx->TL, s, ph, ctx->st, last, S.p0, S.x, S.w,
+                                                S.phiH, S.phik, cap ? S.snap + 3 * N : nullptr,
+                                                S.rn, S.hb, S.aP, S.rk, ucur, ctx->part(PS_MASS));
+        });
+        return;
+    }
     timed(ctx, KC_CORR_FLUX, 10, -1, [&] {
         O::corr_flux(L, ctx->TL, s, ph, ctx->st, S.p0, S.x, S.w, S.phiH, S.phik, S.q,
                      cap ? S.snap + 3 * N : nullptr);
     });
     timed(ctx, KC_CORR_UPDATE, 13, -1, [&] {
-        ctx->nb_mass = O::corr_update(L, ctx->TL, s, ph, ctx->st, corr == ctx->prm.n_corr - 1, S.rn,
-                                      S.phik, S.hb, S.q, S.aP, S.rk, ucur, ctx->part(PS_MASS));
+        ctx->nb_mass = O::corr_update(L, ctx->TL, s, ph, ctx->st, last, S.rn, S.phik, S.hb, S.q,
+                                      S.aP, S.rk, ucur, ctx->part(PS_MASS));
     });
 }
 
