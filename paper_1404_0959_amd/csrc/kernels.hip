@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(kBlock) k_mom_sweep(Phys ph, const DevState* s
 }
 
 // The same sweep as a z-march over a 64 x 8 column tile (n a multiple of 64,
-// n >= 128): each velocity component and p^n are read once per cell from HBM;
+// n >= 64): each velocity component and p^n are read once per cell from HBM;
 // their x-y neighbours of the current plane come from LDS tiles (halo 2), the
 // z neighbours from five-plane register queues; the fluxes phi_x, phi_y of the
 // plane sit in LDS with the one low-side neighbour each needs, phi_z in a
@@ -546,7 +546,7 @@ __global__ void __launch_bounds__(kBlock) k_corr_rhs(
 }
 
 // The corrector set-up as a z-march over a 64 x 8 column tile (n a multiple
-// of 64, n >= 128), for the reason of k_mom_sweep_tiled: w, rho_k, the HbyA x
+// of 64), for the reason of k_mom_sweep_tiled: w, rho_k, the HbyA x
 // and y components and p0 are read once per cell from HBM and their x-y
 // neighbours of the current plane come from halo-2 LDS tiles; the z
 // neighbours of w, rho_k and HbyA_z come from five-plane register queues, of
@@ -868,7 +868,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(Phys ph, DevState* st, int 
     block_partials<1, 0u>(v, part_s);
 }
 
-// Tiled form of the first half for n a multiple of 64 (and >= 128): a block
+// Tiled form of the first half for n a multiple of 64: a block
 // owns a 64 x 8 column tile and marches along z.  The face coefficients
 // K = I4(w) and the direction p = z + beta p_old are read once per cell from
 // HBM: the x-y neighbours of the current plane come from LDS tiles (halo 2 for
@@ -2006,7 +2006,7 @@ Launch make_launch_shaped(int n, int batch, int bx, int cz) {
 }
 
 // ---------------------------------------------------------------- tiled
-// Generic z-march over 64 x 8 column tiles (n a multiple of 64, n >= 128) for
+// Generic z-march over 64 x 8 column tiles (n a multiple of 64) for
 // the field kernels whose cells gather 13-point crosses, for the reason of
 // k_mom_sweep_tiled: each of the K::NS stencil fields is read once per cell
 // from HBM; its x-y neighbours on the current plane come from a halo-2 LDS
@@ -2572,7 +2572,7 @@ Launch make_launch(int n, int batch) {
 
 Launch make_tiled_launch(int n, int batch) {
     Launch L{};
-    if (n < 128 || n % kTX != 0 || n % kTY != 0) return L;   // nblocks = 0: not available
+    if (n < 64 || n % kTX != 0 || n % kTY != 0) return L;   // nblocks = 0: not available
     const int gx = n / kTX, gy = n / kTY;
     int nz = kTiledBlocks / (gx * gy);
     nz = nz < 1 ? 1 : nz;
@@ -2604,7 +2604,7 @@ Launch make_spmv_launch(int n, int batch, int elem_bytes) {
         return L;
     }
     constexpr int TY = kTY * kSpmvRows;
-    if (n < 128 || n % kTX != 0 || n % TY != 0) return L;   // nblocks = 0: not available
+    if (n < 64 || n % kTX != 0 || n % TY != 0) return L;   // nblocks = 0: not available
     const int gx = n / kTX, gy = n / TY;
     int nz = kTiledBlocks / (gx * gy);
     nz = nz < 1 ? 1 : nz;

@@ -32,7 +32,8 @@ Launch make_launch(int n, int batch = 1);
 Launch make_launch_shaped(int n, int batch, int bx, int cz);
 
 // Launch of the LDS-tiled z-marching kernels (64 x 8 threads per block); nblocks
-// is 0 when n is not a multiple of the tile or below 128.
+// is 0 when n is not a multiple of the tile (64 x 8); at n = 64 one tile spans
+// x and its x halo wraps onto itself.
 Launch make_tiled_launch(int n, int batch = 1);
 
 // Launch of the CG first half for fields of elem_bytes per value.  For

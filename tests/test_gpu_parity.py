@@ -162,16 +162,19 @@ def test_step_parity_ragged_and_small(P, ora, n, classes, steps):
     compare_state(P, ora, s, o)
 
 
-def test_step_parity_hit128_tiled(P, ora):
-    """128^3 runs the LDS-tiled z-marching CG kernel (n a multiple of 64)."""
-    case = make_hit_case(128, 3, mach=0.2, stokes=(0.2,))
+@pytest.mark.parametrize("n", [64, 128])
+def test_step_parity_hit128_tiled(P, ora, n):
+    """n a multiple of 64 runs the LDS-tiled z-marching kernels (at 64 one tile
+    spans x and its x halo wraps onto itself)."""
+    case = make_hit_case(n, 3, mach=0.2, stokes=(0.2,))
     o, s, io, ig = run_pair(P, ora, case, 2, p_tol=1e-8)
     compare_state(P, ora, s, o)
 
 
+@pytest.mark.parametrize("n", [64, 128])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_tiled_kernels_match_gathered(P, monkeypatch, precision):
-    """At 128^3 the stencil kernels run as tiled z-marches (the generic k_tiled
+def test_tiled_kernels_match_gathered(P, monkeypatch, precision, n):
+    """At n = 64 and 128 the stencil kernels run as tiled z-marches (the generic k_tiled
     driver, the tiled corrector set-up, momentum sweep and CG first half); with
     PISOC_UNTILED=1 the same step runs the gathered kernels. Both call the same
     cell arithmetic; only reduction order differs, so the CG iteration counts
@@ -179,7 +182,7 @@ def test_tiled_kernels_match_gathered(P, monkeypatch, precision):
     the bound of the FP32 tests, 5e-5 of the spread plus 16 FP32 ulps of the
     magnitude -- a dust density of 1e-3 with a spread of 1e-5 after two steps
     differs by a few ulps of its stored value)."""
-    case = make_hit_case(128, 7, mach=0.5, stokes=(0.1, 0.4))
+    case = make_hit_case(n, 7, mach=0.5, stokes=(0.1, 0.4))
     kw = dict(p_tol=1e-9) if precision == "fp64" else dict(
         p_tol=1e-6, precision=P.FP32_REFINED, inner_tol=1e-6)
     runs = []
