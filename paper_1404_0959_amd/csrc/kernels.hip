@@ -775,15 +775,6 @@ __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
     }
 }
 
-// Zero a field (the inner correction) -- a kernel, not a memset, so that the
-// step can be captured in a graph.
-template <typename T>
-__global__ void k_zero(T* __restrict__ a, size_t count) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < count; i += stride) a[i] = T(0);
-}
-
 // ---------------------------------------------------------------- CG
 // Iteration k, first half.  Totals of the previous kernel's partials give
 // r_k.z_k, ||r_k||^2 (and ||b||^2 when k = 0); the solve stops here when
@@ -2742,10 +2733,6 @@ unsigned Ops<T>::refine(const Launch& L, const Launch& TL, hipStream_t s, const 
     else
         LAUNCH((k_refine<T, false>), L, s, ph, st, x64, d, x64n, b64, w, diag, r32, part_u);
     return L.nblocks;
-}
-template <typename T>
-void Ops<T>::zero(hipStream_t s, T* a, size_t count) {
-    hipLaunchKernelGGL(k_zero<T>, lin_grid(count), dim3(kBlock), 0, s, a, count);
 }
 template <typename T, bool XUPD>
 static void spmv_launch(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,

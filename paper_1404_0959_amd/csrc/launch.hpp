@@ -95,7 +95,6 @@ struct Ops {
                            DevState* st, const double* x64, const T* d, double* x64n,
                            const double* b64, const T* w, const T* diag, T* r32,
                            double* part_u, bool from_zero);
-    static void zero(hipStream_t s, T* a, size_t count);
     // TL: the tiled CG launch of make_spmv_launch (used when TL.nblocks > 0)
     // k >= 1 also applies the previous iteration's x += alpha p; xzero: the
     // solve started from x = 0 without x being written; nb_u: the number of
