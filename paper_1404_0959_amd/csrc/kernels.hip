@@ -249,16 +249,18 @@ __global__ void __launch_bounds__(kBlock) k_mom_sweep(Phys ph, const DevState* s
     END_CELLS
 }
 
-// The same sweep as a z-march over a 64 x 8 column tile (n a multiple of 64,
-// n >= 64): each velocity component and p^n are read once per cell from HBM;
+// The same sweep as a z-march over a 64 x 8 column tile (n a multiple of
+// 64): each velocity component and p^n are read once per cell from HBM;
 // their x-y neighbours of the current plane come from LDS tiles (halo 2), the
 // z neighbours from five-plane register queues; the fluxes phi_x, phi_y of the
 // plane sit in LDS with the one low-side neighbour each needs, phi_z in a
 // two-plane queue.  All loads of plane k + 1 (queue heads, own-cell values and
 // this thread's share of the halo) are issued before plane k's LDS-only
 // barriers.  The per-cell arithmetic is mom_cell, as in k_mom_sweep.
+// (FP32: at least four wavefronts per SIMD, two blocks per CU, with the
+// halo queue in registers)
 template <typename T, bool HBYA>
-__global__ void __launch_bounds__(kTX * kTY) k_mom_sweep_tiled(
+__global__ void __launch_bounds__(kTX * kTY, sizeof(T) == 4 ? 4 : 2) k_mom_sweep_tiled(
     Phys ph, const DevState* st, const T* __restrict__ uin, T* __restrict__ uout,
     const T* __restrict__ phi, const T* __restrict__ aP, const T* __restrict__ s,
     const T* __restrict__ pn, const T* __restrict__ rk, T* __restrict__ w, T* __restrict__ p0) {
@@ -337,15 +339,26 @@ __global__ void __launch_bounds__(kTX * kTY) k_mom_sweep_tiled(
     fzq[0] = phi[2 * N + col + nn * wr(k0 - 1)];
     fzq[1] = phi[2 * N + col + nn * k0];
     T cfx = phi[col + nn * k0], cfy = phi[N + col + nn * k0], ca = aP[col + nn * k0];
-    T cs[3], crk = HBYA ? rk[col + nn * k0] : T(0), ch[kPer];
+    T cs[3], crk = HBYA ? rk[col + nn * k0] : T(0);
 #pragma unroll
     for (int m = 0; m < 3; ++m) cs[m] = s[(size_t)m * N + col + nn * k0];
+    auto clampk = [](int a, int hi) { return a < hi ? a : hi; };
+    // halo values of planes kk .. kk + kHQ - 1 (hq[.][0] goes to LDS at plane
+    // kk).  FP32: a halo value is loaded with the owner tile's queue head of
+    // the same plane, four planes ahead, so that both reads of the line fall
+    // together in L2; FP64 loads it two planes ahead (its registers are full)
+    constexpr int kHQ = sizeof(T) == 4 ? 3 : 1;
+    T hq[kPer][kHQ];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) ch[q] = hsrc[q][nn * (size_t)k0 + hoff[q]];
+    for (int q = 0; q < kPer; ++q)
+#pragma unroll
+        for (int t = 0; t < kHQ; ++t)
+            hq[q][t] = hsrc[q][nn * (size_t)wr(clampk(k0 + t, k1 - 1)) + hoff[q]];
     // values of plane k0 + 1 and the queue head at k0 + 3, rotated in after plane k0
     T nu[3], np = T(0), nfz, nfx, nfy, na, ns[3], nrk = T(0), nh[kPer];
-    auto prefetch = [&](int kq, int kv) {      // queue head at plane kq, values at plane kv
-        const size_t pq3 = nn * (size_t)wr(kq), pv = nn * (size_t)wr(kv);
+    // queue heads at plane kq, halo values at kh, own values at kv
+    auto prefetch = [&](int kq, int kh, int kv) {
+        const size_t pq3 = nn * (size_t)wr(kq), phh = nn * (size_t)wr(kh), pv = nn * (size_t)wr(kv);
 #pragma unroll
         for (int m = 0; m < 3; ++m) nu[m] = uin[(size_t)m * N + col + pq3];
         if (!HBYA) np = pn[col + pq3];
@@ -357,9 +370,10 @@ __global__ void __launch_bounds__(kTX * kTY) k_mom_sweep_tiled(
         for (int m = 0; m < 3; ++m) ns[m] = s[(size_t)m * N + col + pv];
         if (HBYA) nrk = rk[col + pv];
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) nh[q] = hsrc[q][pv + hoff[q]];
+        for (int q = 0; q < kPer; ++q) nh[q] = hsrc[q][phh + hoff[q]];
     };
-    prefetch(k0 + 3, k0 + 1);
+    // last planes the chunk needs: queue heads k1 + 1, halo and own values k1 - 1
+    prefetch(clampk(k0 + 3, k1 + 1), clampk(k0 + kHQ, k1 - 1), clampk(k0 + 1, k1 - 1));
     for (int kk = k0; kk < k1; ++kk) {
         const size_t pl = nn * (size_t)kk;
         // plane kk into LDS
@@ -369,7 +383,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_mom_sweep_tiled(
         FX(ty, tx + 1) = cfx;
         FY(ty + 1, tx) = cfy;
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) lds[hdst[q]] = ch[q];
+        for (int q = 0; q < kPer; ++q) lds[hdst[q]] = hq[q][0];
         lds_barrier();
         T u[3][13], pv[13], fp[3], fm[3];
 #pragma unroll
@@ -439,8 +453,12 @@ __global__ void __launch_bounds__(kTX * kTY) k_mom_sweep_tiled(
         for (int m = 0; m < 3; ++m) cs[m] = ns[m];
         crk = nrk;
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) ch[q] = nh[q];
-        prefetch(kk + 4, kk + 2);
+        for (int q = 0; q < kPer; ++q) {
+#pragma unroll
+            for (int t = 0; t + 1 < kHQ; ++t) hq[q][t] = hq[q][t + 1];
+            hq[q][kHQ - 1] = nh[q];
+        }
+        prefetch(clampk(kk + 4, k1 + 1), clampk(kk + 1 + kHQ, k1 - 1), clampk(kk + 2, k1 - 1));
     }
 }
 
