@@ -106,6 +106,35 @@ __global__ void __launch_bounds__(kBlock) k_cfl(Phys ph, const DevState* st, con
 // dt_fixed) from the Courant partials; density predictor
 // rho* = rho^n - dt div(phi^n); momentum diagonal
 // a_P = rho*/dt + (9/16) div(phi^n) + 6 mu / h^2; div u^n (Gauss-I4); p(rho^n).
+__device__ inline double predict_dt(double sigma, double dt_prev, double dt_fixed, double cfl,
+                                    double growth, double dt_max) {
+    if (dt_fixed > 0.0) return dt_fixed;
+    double dtd = sigma > 0.0 ? cfl / sigma : __builtin_inf();
+    if (growth * dt_prev < dtd) dtd = growth * dt_prev;
+    if (dt_max > 0.0 && dt_max < dtd) dtd = dt_max;
+    return dtd;
+}
+
+// From the face fluxes of the cell (own fp, lower fm) and u^n_d on the line
+// along d (ul[d][5]): rho*, a_P, div u^n; p(rho^n) from rho^n.
+template <typename T>
+__device__ inline void predict_cell(const T (&fp)[3], const T (&fm)[3], const T (&ul)[3][5], T rnP,
+                                    T dt, T inv_V, T inv_h, T diag_visc, T rref, double pref,
+                                    double gamma, T& rs, T& a, T& divu, T& pn) {
+    T dphi = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dphi += fp[d] - fm[d];
+    dphi *= inv_V;
+    const T r = rnP - dt * dphi;
+    rs = r;
+    a = (rref + r) / dt + T(0.5625) * dphi + diag_visc;
+    T du = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) du += i4l<T>(ul[d], 0) - i4l<T>(ul[d], -1);
+    divu = du * inv_h;
+    pn = pdev(rnP, (double)rref, pref, gamma);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_predict(Phys ph, DevState* st, const double* part_cfl,
                                                     unsigned nb, double dt_fixed, double cfl,
@@ -118,15 +147,7 @@ __global__ void __launch_bounds__(kBlock) k_predict(Phys ph, DevState* st, const
     const size_t N = ncell(ph);
     double sg[1];
     reduce_member<1, 1u>(part_cfl, nb, ph.batch, mem_, sg);
-    const double dt_prev = (st + mem_)->dt_prev;
-    double dtd;
-    if (dt_fixed > 0.0) {
-        dtd = dt_fixed;
-    } else {
-        dtd = sg[0] > 0.0 ? cfl / sg[0] : __builtin_inf();
-        if (growth * dt_prev < dtd) dtd = growth * dt_prev;
-        if (dt_max > 0.0 && dt_max < dtd) dtd = dt_max;
-    }
+    const double dtd = predict_dt(sg[0], (st + mem_)->dt_prev, dt_fixed, cfl, growth, dt_max);
     if (MEMBER_FIRST()) {
         if (!(dtd > 0.0) || !isfinite(dtd)) (st + mem_)->flags |= 16;  // bad dt
         (st + mem_)->sigma = sg[0];
@@ -136,18 +157,22 @@ __global__ void __launch_bounds__(kBlock) k_predict(Phys ph, DevState* st, const
     const T inv_V = (T)ph.inv_V, inv_h = (T)ph.inv_h;
     const T diag_visc = (T)(6.0 * ph.mu * ph.inv_h2);
     FOR_CELLS(ph)
-    T dphi = T(0);
+    T fp[3], fm[3], ul[3][5];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) dphi += phi[d * N + P] - phi[d * N + c.sh(d, -1)];
-    dphi *= inv_V;
-    T r = rn[P] - dt * dphi;
+    for (int d = 0; d < 3; ++d) {
+        fp[d] = phi[d * N + P];
+        fm[d] = phi[d * N + c.sh(d, -1)];
+        gather_line(un + d * N, c, d, ul[d]);
+    }
+    const T rnP = rn[P];
+    loads_issued();
+    T r, a, dv, p;
+    predict_cell(fp, fm, ul, rnP, dt, inv_V, inv_h, diag_visc, (T)(st + mem_)->rho_ref,
+                 (st + mem_)->p_ref, ph.gamma, r, a, dv, p);
     rs[P] = r;
-    aP[P] = ((T)(st + mem_)->rho_ref + r) / dt + T(0.5625) * dphi + diag_visc;
-    T du = T(0);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) du += i4(un + d * N, c, d, 0) - i4(un + d * N, c, d, -1);
-    divu[P] = du * inv_h;
-    pn[P] = pdev(rn[P], (st + mem_)->rho_ref, (st + mem_)->p_ref, ph.gamma);
+    aP[P] = a;
+    divu[P] = dv;
+    pn[P] = p;
     END_CELLS
 }
 
@@ -2557,6 +2582,55 @@ struct TiledCorrFluxUpdate : TiledBase<T> {
     }
 };
 
+// The predictor: dt from the Courant partials (every block reduces them, as
+// k_predict), then predict_cell; the member's first thread stores dt.
+template <typename T>
+struct TiledPredict : TiledBase<T> {
+    static constexpr int NS = 3;          // u^n
+    static constexpr bool FACES = true;   // phi^n
+    const T* sf[3];
+    const DevState* st0;                  // member 0's state
+    const double* part_cfl;
+    unsigned nb_cfl;
+    double dt_fixed, cfl, growth, dt_max;
+    const T* rn;
+    T *rs, *aP, *divu, *pn;
+    double dtd, sigma, pref, gamma;
+    T dt, inv_V, inv_h, diag_visc, rref;
+    struct Pts { T rn; };
+    __device__ void member(const Phys& ph, const DevState* d) {
+        double sg[1];
+        reduce_member<1, 1u>(part_cfl, nb_cfl, ph.batch, (int)(d - st0), sg);
+        sigma = sg[0];
+        dtd = predict_dt(sigma, d->dt_prev, dt_fixed, cfl, growth, dt_max);
+        dt = (T)dtd;
+        inv_V = (T)ph.inv_V;
+        inv_h = (T)ph.inv_h;
+        diag_visc = (T)(6.0 * ph.mu * ph.inv_h2);
+        rref = (T)d->rho_ref;
+        pref = d->p_ref;
+        gamma = ph.gamma;
+    }
+    __device__ Pts load(size_t P) const { return {rn[P]}; }
+    __device__ void cell(size_t P, const T (&v)[3][13], const T (&fp)[3], const T (&fm)[3],
+                         const Pts& p, double*) const {
+        T ul[3][5];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cross_line(v[d], d, ul[d]);
+        T r, a, dv, pp;
+        predict_cell(fp, fm, ul, p.rn, dt, inv_V, inv_h, diag_visc, rref, pref, gamma, r, a, dv, pp);
+        rs[P] = r;
+        aP[P] = a;
+        divu[P] = dv;
+        pn[P] = pp;
+    }
+    __device__ void first(DevState* d) const {
+        if (!(dtd > 0.0) || !isfinite(dtd)) d->flags |= 16;  // bad dt
+        d->sigma = sigma;
+        d->dt = dtd;
+    }
+};
+
 // Launch of k_tiled over the tiled launch TL; returns its block count (the
 // number of partials a reducing functor writes).
 template <typename T, class K>
@@ -2662,10 +2736,29 @@ void Ops<T>::cfl(const Launch& L, hipStream_t s, const Phys& ph, const DevState*
     LAUNCH(k_cfl<T>, L, s, ph, st, r, phi, part);
 }
 template <typename T>
-void Ops<T>::predict(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
-                     const double* part_cfl, double dt_fixed, double cfl, double growth,
-                     double dt_max, const T* rn, const T* un, const T* phi, T* rs, T* aP, T* divu,
-                     T* pn) {
+void Ops<T>::predict(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                     DevState* st, const double* part_cfl, double dt_fixed, double cfl,
+                     double growth, double dt_max, const T* rn, const T* un, const T* phi, T* rs,
+                     T* aP, T* divu, T* pn) {
+    if (TL.nblocks) {
+        TiledPredict<T> k{};
+        for (int d = 0; d < 3; ++d) k.sf[d] = un + d * ph.NT;
+        k.face = phi;
+        k.st0 = st;
+        k.part_cfl = part_cfl;
+        k.nb_cfl = L.nblocks;
+        k.dt_fixed = dt_fixed;
+        k.cfl = cfl;
+        k.growth = growth;
+        k.dt_max = dt_max;
+        k.rn = rn;
+        k.rs = rs;
+        k.aP = aP;
+        k.divu = divu;
+        k.pn = pn;
+        tiled_launch<T>(TL, s, ph, st, k);
+        return;
+    }
     LAUNCH(k_predict<T>, L, s, ph, st, part_cfl, L.nblocks, dt_fixed, cfl, growth, dt_max, rn, un,
            phi, rs, aP, divu, pn);
 }

@@ -68,10 +68,12 @@ struct Ops {
                          const T* r, const T* u, T* phi);
     static void cfl(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                     const T* r, const T* phi, double* part);
-    static void predict(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
-                        const double* part_cfl, double dt_fixed, double cfl, double growth,
-                        double dt_max, const T* rn, const T* un, const T* phi, T* rs, T* aP,
-                        T* divu, T* pn);
+    // TL: the tiled z-march when available (the Courant partials come from
+    // cfl over L)
+    static void predict(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                        DevState* st, const double* part_cfl, double dt_fixed, double cfl,
+                        double growth, double dt_max, const T* rn, const T* un, const T* phi,
+                        T* rs, T* aP, T* divu, T* pn);
     // Field kernels taking TL run as k_tiled z-marches when TL.nblocks > 0;
     // those that write partials return how many (blocks of the launch used).
     static void mom_source(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,

@@ -465,7 +465,7 @@ void enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S) {
     clear_flags(s, st, ctx->batch);
     timed(ctx, KC_CFL, 4, -1, [&] { O::cfl(L, s, ph, st, S.rn, S.phin, ctx->part(PS_CFL)); });
     timed(ctx, KC_PREDICT, 11, -1, [&] {
-        O::predict(L, s, ph, st, ctx->part(PS_CFL), p.dt_fixed, p.cfl, p.dt_growth, p.dt_max, S.rn,
+        O::predict(L, ctx->TL, s, ph, st, ctx->part(PS_CFL), p.dt_fixed, p.cfl, p.dt_growth, p.dt_max, S.rn,
                    S.un, S.phin, S.rk, S.aP, S.divu, S.pn);
     });
     timed(ctx, KC_MOM_SOURCE, 8, -1,
