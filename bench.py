@@ -193,9 +193,7 @@ KERNEL_SOURCES = ("kernels.hip", "device.hpp", "launch.hpp", "net.hip")
 TRAFFIC_NAME = {("k_pcg_spmv", "f32+f64"): ("k_pcg_spmv_rows<float, 4, false>",
                                            "k_pcg_spmv_rows<float, 4, true>"),
                 ("k_pcg_spmv", "f64"): ("k_pcg_spmv_tiled<double, 1, false>",
-                                       "k_pcg_spmv_tiled<double, 1, true>"),
-                ("k_pcg_update", "f32+f64"): ("k_pcg_update<float>",),
-                ("k_pcg_update", "f64"): ("k_pcg_update<double>",)}
+                                       "k_pcg_spmv_tiled<double, 1, true>")}
 
 
 def measured_traffic(kernel, dtype, n):

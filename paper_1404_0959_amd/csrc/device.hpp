@@ -34,11 +34,9 @@ struct Phys {
 // the host between iterations.
 struct PcgState {
     double bb;        // reference ||b||^2 of the current solve
-    double rzh[2];    // r.z of iterate k in slot k & 1
     double rr;        // ||r||^2 of the last checked iterate
     double tol2;      // tol^2 of the current (inner) solve
     double tol_final; // p_tol^2: the requested relative residual, squared
-    double alpha;     // alpha of the last second half; the next first half applies it to x
     int32_t it_stop;  // iteration index at which the solve stopped (kIterInf: running)
     int32_t maxit;
     int32_t iters;

@@ -819,72 +819,132 @@ __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
 }
 
 // ---------------------------------------------------------------- CG
-// Iteration k, first half.  Totals of the previous kernel's partials give
-// r_k.z_k, ||r_k||^2 (and ||b||^2 when k = 0); the solve stops here when
-// ||r_k||^2 <= tol^2 ||b||^2 or k = maxit (every block takes the same
-// decision).  Otherwise: direction p_k = z_k + beta_{k-1} p_{k-1} with
-// z = r / diag recomputed on the stencil (not stored), q = M p_k with the face
-// coefficients K = I4(w) formed on the fly, and partial sums of p_k.q.
-// XUPD (k >= 1): the previous iteration's x += alpha_{k-1} p_{k-1} is applied
-// here, where p_{k-1} is read anyway, also when the solve stops; with xzero
-// (the solve started from x = 0, not written) it writes x at k = 1 and, on a
-// stop at k = 0, zeroes it.
-template <typename T, bool XUPD>
-__global__ void __launch_bounds__(kBlock) k_pcg_spmv(Phys ph, DevState* st, int k,
-                                                     const T* __restrict__ r, const T* __restrict__ diag,
-                                                     const T* __restrict__ w, const T* __restrict__ pold,
-                                                     T* __restrict__ pnew, T* __restrict__ q,
-                                                     T* __restrict__ x, const double* part_u,
-                                                     double* part_s, unsigned nb, int fresh, int maxit,
-                                                     int xzero) {
-    MEMBER(ph)
-    // it_stop == k is this launch's own decision, written by the member's
-    // first block: the other blocks must still take the stop path below
-    if (k > (st + mem_)->pcg.it_stop) return;
-    double t[3];
-    reduce_member<3, 0u>(part_u, nb, ph.batch, mem_, t);
-    const double rz = t[0], rr = t[1];
+// Jacobi-PCG with one kernel per iteration.  Iteration k >= 1 forms, on the
+// stencil, r_k = r_{k-1} - alpha_{k-1} q_{k-1}, z_k = r_k / diag (not stored)
+// and the direction p_k = z_k + beta_k p_{k-1}; iteration 0 takes p_0 = z_0.
+// Then q_k = M p_k with the face coefficients K = I4(w) formed on the fly; the
+// kernel stores r_k, p_k and q_k, applies x_k = x_{k-1} + alpha_{k-1} p_{k-1}
+// (p_{k-1} is read anyway; also on the stop path) and writes the partial sums
+// from which the next iteration takes its scalars (cg_head).  The iterates
+// are those of textbook PCG; r_k.z_k and ||r_k||^2 are expanded from sums of
+// iteration k-1 instead of being summed over r_k, so one global reduction per
+// iteration suffices.  r, p and q alternate between two buffers (iteration k
+// reads the k-1 values on the stencil while writing its own).  With xzero
+// (the solve started from x = 0, not written) the kernel writes x at k = 1
+// and, on a stop at k = 0, zeroes it.
+
+// Partial-sum columns of iteration k (FP64 sums of products of the stored
+// values): p.q, q.z, q.(q/diag), q.r, q.q, r.z, r.r over r_k, z_k = r_k / diag
+// (the z of the direction), p_k, q_k.
+enum CgCol { CG_PQ, CG_QZ, CG_QQD, CG_QR, CG_QQ, CG_RZ, CG_RR, CG_COLS };
+static_assert(CG_COLS == kCgCols, "CG partial columns");
+
+// The Jacobi preconditioner z = r / diag is applied as r * jinv(diag): in
+// FP32 the hardware reciprocal (within 1 ulp; the preconditioner stays a
+// positive diagonal), in FP64 the rounded 1 / diag.  Every block forms a
+// cell's z with the same expression, so all see the same direction p.
+__device__ inline float jinv(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ inline double jinv(double d) { return 1.0 / d; }
+
+// y = q / diag as y = q * jinv(diag)
+template <typename T>
+__device__ inline void cg_accumulate(double (&v)[CG_COLS], T p, T q, T r, T z, T id) {
+    const double qd = (double)q, rd = (double)r, zd = (double)z, yd = (double)(q * id);
+    v[CG_PQ] += (double)p * qd;
+    v[CG_QZ] += qd * zd;
+    v[CG_QQD] += qd * yd;
+    v[CG_QR] += qd * rd;
+    v[CG_QQ] += qd * qd;
+    v[CG_RZ] += rd * zd;
+    v[CG_RR] += rd * rd;
+}
+
+// Scalars of iteration k, bitwise the same in every block of the member.
+// k = 0: ||r_0||^2 (and ||b||^2 of a fresh solve) from the set-up kernel's
+// partials (r.z, r.r, b.b).  k >= 1: from the partials of iteration k-1,
+// alpha_{k-1} = r.z / p.q and, with r_k = r_{k-1} - alpha_{k-1} q_{k-1},
+//   r_k.z_k   = r.z - 2 alpha q.z + alpha^2 q.(q/diag),
+//   ||r_k||^2 = r.r - 2 alpha q.r + alpha^2 q.q,
+// each one step from sums over the stored r_{k-1} (no drift accumulates over
+// iterations); beta_k = r_k.z_k / r_{k-1}.z_{k-1}.  Stop at
+// ||r_k||^2 <= tol^2 ||b||^2 or k = maxit; `recorder` (one thread of the
+// member) writes the iteration to the member state.
+struct CgHead {
+    double alpha, beta, rr;
+    bool stop;
+};
+__device__ inline CgHead cg_head(const Phys& ph, PcgState& g, bool recorder, int mem, int k,
+                                 const double* part_in, unsigned nb_in, int fresh, int maxit) {
+    CgHead h{0.0, 0.0, 0.0, false};
     // reference ||b||^2: from this system's partials on the first iteration of
     // a fresh solve, else the stored one (later refinement rounds measure
-    // against the original right-hand side); tolerance from the member state
+    // against the original right-hand side)
     const bool newb = fresh && k == 0;
-    const double bb = newb ? t[2] : (st + mem_)->pcg.bb;
-    const double tol2 = (st + mem_)->pcg.tol2;
-    const bool conv = rr <= tol2 * bb;
-    const bool stop = conv || k >= maxit;
-    if (MEMBER_FIRST()) {
-        PcgState& g = (st + mem_)->pcg;
-        g.rr = rr;
+    double bb;
+    if (k == 0) {
+        double t[3];
+        reduce_member<3, 0u>(part_in, nb_in, ph.batch, mem, t);
+        h.rr = t[1];
+        bb = newb ? t[2] : g.bb;
+    } else {
+        double t[CG_COLS];
+        reduce_member<CG_COLS, 0u>(part_in, nb_in, ph.batch, mem, t);
+        const double a = t[CG_RZ] / t[CG_PQ];
+        const double rz = t[CG_RZ] - 2.0 * a * t[CG_QZ] + a * a * t[CG_QQD];
+        const double rr = t[CG_RR] - 2.0 * a * t[CG_QR] + a * a * t[CG_QQ];
+        h.alpha = a;
+        h.beta = rz / t[CG_RZ];
+        h.rr = rr < 0.0 ? 0.0 : rr;   // cancellation at the rounding floor; NaN stays NaN
+        bb = g.bb;
+    }
+    const bool conv = h.rr <= g.tol2 * bb;
+    h.stop = conv || k >= maxit;
+    if (recorder) {
+        g.rr = h.rr;
         g.iters = k;
-        g.rzh[k & 1] = rz;
         if (newb) g.bb = bb;
-        if (stop) {
+        if (h.stop) {
             g.it_stop = k;
             g.converged = conv ? 1 : 0;
         }
     }
-    const T alpha = XUPD ? (T)(st + mem_)->pcg.alpha : T(0);
-    const bool xset = XUPD && k == 1 && xzero;
+    return h;
+}
+
+// Gathered form (any n).  UPD: k >= 1.
+template <typename T, bool UPD>
+__global__ void __launch_bounds__(kBlock) k_pcg_spmv(
+    Phys ph, DevState* st, int k, const T* __restrict__ rin, T* __restrict__ rout,
+    const T* __restrict__ diag, const T* __restrict__ w, const T* __restrict__ pold,
+    T* __restrict__ pnew, const T* __restrict__ qold, T* __restrict__ q, T* __restrict__ x,
+    const double* part_in, unsigned nb_in, double* part_out, int fresh, int maxit, int xzero) {
+    MEMBER(ph)
+    // it_stop == k is this launch's own decision, written by the member's
+    // first block: the other blocks must still take the stop path below
+    if (k > (st + mem_)->pcg.it_stop) return;
+    const CgHead h = cg_head(ph, (st + mem_)->pcg, MEMBER_FIRST(), mem_, k, part_in, nb_in, fresh,
+                             maxit);
+    const T alpha = (T)h.alpha, beta = (T)h.beta;
+    const bool xset = UPD && k == 1 && xzero;
     auto xnew = [&](T xo, T po) { return xset ? alpha * po : xo + alpha * po; };
-    if (stop) {
-        if (XUPD || xzero) {
+    if (h.stop) {
+        if (UPD || xzero) {
             FOR_CELLS(ph)
-            x[P] = XUPD ? xnew(x[P], pold[P]) : T(0);
+            x[P] = UPD ? xnew(x[P], pold[P]) : T(0);
             END_CELLS
         }
         return;
     }
-    const T beta = k == 0 ? T(0) : (T)(rz / (st + mem_)->pcg.rzh[(k - 1) & 1]);
-    const bool first = k == 0;
     const T inv_h2 = (T)ph.inv_h2;
-    double v[1] = {0.0};
+    double v[CG_COLS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     FOR_CELLS(ph)
-    if (XUPD) x[P] = xnew(x[P], pold[P]);
+    auto res = [&](size_t Q) -> T { return UPD ? rin[Q] - alpha * qold[Q] : rin[Q]; };
     auto dir = [&](size_t Q) -> T {
-        T z = r[Q] / diag[Q];
-        return first ? z : z + beta * pold[Q];
+        const T z = res(Q) * jinv(diag[Q]);
+        return UPD ? z + beta * pold[Q] : z;
     };
-    const T pP = dir(P);
+    const T rP = res(P), dP = diag[P], iP = jinv(dP), zP = rP * iP;
+    const T pP = UPD ? zP + beta * pold[P] : zP;   // as dir(P)
     // difference form psi/dt p_P + sum K (p_P - p_nb) / h^2 (no cancellation
     // between the diagonal and the neighbour sum for smooth p)
     T lap = T(0), sumK = T(0);
@@ -894,53 +954,34 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(Phys ph, DevState* st, int 
         lap += kp * (pP - dir(c.sh(d, 1))) + km * (pP - dir(c.sh(d, -1)));
         sumK += kp + km;
     }
-    const T qP = (diag[P] - sumK * inv_h2) * pP + lap * inv_h2;
+    const T qP = (dP - sumK * inv_h2) * pP + lap * inv_h2;
+    if (UPD) {
+        rout[P] = rP;
+        x[P] = xnew(x[P], pold[P]);
+    }
     pnew[P] = pP;
     q[P] = qP;
-    v[0] += (double)pP * (double)qP;
+    cg_accumulate(v, pP, qP, rP, zP, iP);
     END_CELLS
-    block_partials<1, 0u>(v, part_s);
+    block_partials<CG_COLS, 0u>(v, part_out);
 }
 
-// Tiled form of the first half for n a multiple of 64: a block
-// owns a 64 x 8 column tile and marches along z.  The face coefficients
-// K = I4(w) and the direction p = z + beta p_old are read once per cell from
-// HBM: the x-y neighbours of the current plane come from LDS tiles (halo 2 for
-// w, 1 for p), the z neighbours from per-thread register queues.
-template <typename T, int RPT, bool XUPD>
+// Tiled form for n a multiple of 64: a block owns a 64 x 8 column tile and
+// marches along z.  Each of r, q, p_old, diag and w is read once per cell
+// from HBM: the x-y neighbours of the current plane come from LDS tiles (halo
+// 2 for w; halo 1 for the direction p, formed from r, q, p_old and diag at
+// the halo cells), the z neighbours from per-thread register queues.
+template <typename T, int RPT, bool UPD>
 __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
-    Phys ph, DevState* st, int k, const T* __restrict__ r, const T* __restrict__ diag,
-    const T* __restrict__ w, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ q,
-    T* __restrict__ x, const double* part_u, unsigned nb_u, double* part_s, int fresh, int maxit,
-    int xzero) {
+    Phys ph, DevState* st, int k, const T* __restrict__ rin, T* __restrict__ rout,
+    const T* __restrict__ diag, const T* __restrict__ w, const T* __restrict__ pold,
+    T* __restrict__ pnew, const T* __restrict__ qold, T* __restrict__ q, T* __restrict__ x,
+    const double* part_in, unsigned nb_in, double* part_out, int fresh, int maxit, int xzero) {
     MEMBER(ph)
-    // it_stop == k is this launch's own decision, written by the member's
-    // first block: the other blocks must still take the stop path below
-    if (k > (st + mem_)->pcg.it_stop) return;
-    double t[3];
-    reduce_member<3, 0u>(part_u, nb_u, ph.batch, mem_, t);
-    const double rz = t[0], rr = t[1];
-    // reference ||b||^2: from this system's partials on the first iteration of
-    // a fresh solve, else the stored one (later refinement rounds measure
-    // against the original right-hand side); tolerance from the member state
-    const bool newb = fresh && k == 0;
-    const double bb = newb ? t[2] : (st + mem_)->pcg.bb;
-    const double tol2 = (st + mem_)->pcg.tol2;
-    const bool conv = rr <= tol2 * bb;
-    const bool stop = conv || k >= maxit;
-    if (MEMBER_FIRST()) {
-        PcgState& g = (st + mem_)->pcg;
-        g.rr = rr;
-        g.iters = k;
-        g.rzh[k & 1] = rz;
-        if (newb) g.bb = bb;
-        if (stop) {
-            g.it_stop = k;
-            g.converged = conv ? 1 : 0;
-        }
-    }
-    const T beta = k == 0 ? T(0) : (T)(rz / (st + mem_)->pcg.rzh[(k - 1) & 1]);
-    const bool first = k == 0;
+    if (k > (st + mem_)->pcg.it_stop) return;   // see k_pcg_spmv
+    const CgHead h = cg_head(ph, (st + mem_)->pcg, MEMBER_FIRST(), mem_, k, part_in, nb_in, fresh,
+                             maxit);
+    const T alpha = (T)h.alpha, beta = (T)h.beta;
     const T inv_h2 = (T)ph.inv_h2;
     const int n = ph.n, cz = ph.cz;
     constexpr int TY = kTY * RPT;               // tile rows; thread row ty owns rows ty + e kTY
@@ -949,18 +990,16 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     const int k0 = bz_ * cz;
     const int k1 = k0 + cz < n ? k0 + cz : n;
     const size_t nn = (size_t)n * n;
-    // the previous iteration's x update (see k_pcg_spmv)
-    const T alpha = XUPD ? (T)(st + mem_)->pcg.alpha : T(0);
-    const bool xset = XUPD && k == 1 && xzero;
+    const bool xset = UPD && k == 1 && xzero;
     auto xnew = [&](T xo, T po) { return xset ? alpha * po : xo + alpha * po; };
-    if (stop) {
-        if (XUPD || xzero) {
+    if (h.stop) {
+        if (UPD || xzero) {
 #pragma unroll
             for (int e = 0; e < RPT; ++e) {
                 const size_t c0 = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty + e * kTY);
                 for (int kk = k0; kk < k1; ++kk) {
                     const size_t Q = c0 + nn * (size_t)kk;
-                    x[Q] = XUPD ? xnew(x[Q], pold[Q]) : T(0);
+                    x[Q] = UPD ? xnew(x[Q], pold[Q]) : T(0);
                 }
             }
         }
@@ -969,14 +1008,14 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     __shared__ T ws[TY + 4][kTX + 4];
     __shared__ T ps[TY + 2][kTX + 2];
     auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
-    auto dirv = [&](size_t Q) -> T {
-        const T zz = r[Q] / diag[Q];
-        return first ? zz : zz + beta * pold[Q];
-    };
+    // r_k and p_k of a cell from its r_{k-1}, q_{k-1}, diag, p_{k-1}
+    auto resf = [&](T ro, T qo) -> T { return UPD ? ro - alpha * qo : ro; };
+    auto dirf = [&](T z, T po) -> T { return UPD ? z + beta * po : z; };
     size_t col[RPT];
-    T wq0[RPT], wq1[RPT], wq2[RPT], wq3[RPT], wq4[RPT], pm[RPT], pc[RPT], dc[RPT];
-    T rn1[RPT], dn1[RPT], on1[RPT];
-    T oc[RPT], xc[RPT], xn1[RPT];   // XUPD: raw p_old and x of the current plane, x one plane ahead
+    T wq0[RPT], wq1[RPT], wq2[RPT], wq3[RPT], wq4[RPT], pm[RPT], pc[RPT], rc[RPT], zc[RPT], dc[RPT];
+    T ic[RPT];   // jinv(diag) of the current plane
+    T rn1[RPT], qn1[RPT], dn1[RPT], on1[RPT];
+    T oc[RPT], xc[RPT], xn1[RPT];   // UPD: p_old and x of the current plane, x one plane ahead
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
         col[e] = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty + e * kTY);
@@ -984,13 +1023,15 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
         wq1[e] = w[col[e] + nn * wr(k0 - 1)];
         wq2[e] = w[col[e] + nn * k0];
         wq3[e] = w[col[e] + nn * wr(k0 + 1)];
-        pm[e] = dirv(col[e] + nn * wr(k0 - 1));
-        pc[e] = dirv(col[e] + nn * k0);
-        dc[e] = diag[col[e] + nn * k0];
-        if (XUPD) {
-            oc[e] = pold[col[e] + nn * k0];
-            xc[e] = x[col[e] + nn * k0];
-        }
+        const size_t Qm = col[e] + nn * wr(k0 - 1), Q0 = col[e] + nn * k0;
+        pm[e] = dirf(resf(rin[Qm], UPD ? qold[Qm] : T(0)) * jinv(diag[Qm]), UPD ? pold[Qm] : T(0));
+        rc[e] = resf(rin[Q0], UPD ? qold[Q0] : T(0));
+        dc[e] = diag[Q0];
+        ic[e] = jinv(dc[e]);
+        zc[e] = rc[e] * ic[e];
+        oc[e] = UPD ? pold[Q0] : T(0);
+        pc[e] = dirf(zc[e], oc[e]);
+        if (UPD) xc[e] = x[Q0];
     }
     // this thread's halo cell, if any (same x-y position on every plane):
     // w rows j0-2, j0-1, j0+TY, j0+TY+1; w columns i0-2, i0-1, i0+64, i0+65;
@@ -1000,10 +1041,10 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     int hkind = 0, hy = 0, hx = 0;
     size_t hoff = 0;
     if (tid < nWR) {
-        const int row = tid / kTX, x = tid - row * kTX;
+        const int row = tid / kTX, xx = tid - row * kTX;
         hy = row < 2 ? row : TY + row;
-        hx = x + 2;
-        hoff = base_ + (size_t)(i0 + x) + (size_t)n * wr(j0 - 2 + hy);
+        hx = xx + 2;
+        hoff = base_ + (size_t)(i0 + xx) + (size_t)n * wr(j0 - 2 + hy);
         hkind = 1;
     } else if (tid < nWR + nWC) {
         const int t2 = tid - nWR, c4 = t2 / TY, y = t2 - c4 * TY;
@@ -1012,10 +1053,10 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
         hoff = base_ + (size_t)wr(i0 - 2 + hx) + (size_t)n * (j0 + y);
         hkind = 1;
     } else if (tid < nWR + nWC + nPR) {
-        const int t3 = tid - nWR - nWC, row = t3 / kTX, x = t3 - row * kTX;
+        const int t3 = tid - nWR - nWC, row = t3 / kTX, xx = t3 - row * kTX;
         hy = row == 0 ? 0 : TY + 1;
-        hx = x + 1;
-        hoff = base_ + (size_t)(i0 + x) + (size_t)n * wr(j0 - 1 + hy);
+        hx = xx + 1;
+        hoff = base_ + (size_t)(i0 + xx) + (size_t)n * wr(j0 - 1 + hy);
         hkind = 2;
     } else if (tid < nWR + nWC + nPR + nPC) {
         const int t4 = tid - nWR - nWC - nPR, c2 = t4 / TY, y = t4 - c2 * TY;
@@ -1024,49 +1065,69 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
         hoff = base_ + (size_t)wr(i0 - 1 + hx) + (size_t)n * (j0 + y);
         hkind = 2;
     }
-    // Software pipeline: the loads of plane kk + 1 (w at kk + 3; r, diag, p_old
-    // at kk + 2; this thread's halo cell of plane kk + 1) are issued before the
-    // LDS stores and barrier of plane kk, so their latency overlaps its work.
-    // Every load is unconditional and in bounds (threads without a halo cell
-    // read their own), so no branch forces the loads to drain early.
-    const T* hsrc = hkind == 1 ? w : r;                 // w halo, or r of the p halo
+    // Software pipeline: the loads of plane kk + 1 (w at kk + 3; r, q, diag,
+    // p_old at kk + 2; this thread's halo cell of plane kk + 1) are issued
+    // before the LDS stores and barrier of plane kk, so their latency overlaps
+    // its work.  Every load is unconditional and in bounds (threads without a
+    // halo cell read their own), so no branch forces the loads to drain early.
+    // the p halo reads r, diag, q, p_old; a w-halo thread points its other
+    // three loads at its w cell, a thread without a halo cell all four at its
+    // own r cell (cache hits, no extra HBM traffic)
+    const T* hsrc = hkind == 1 ? w : rin;
+    const T* hdsrc = hkind == 2 ? diag : hsrc;
+    const T* hqsrc = hkind == 2 ? qold : hsrc;
+    const T* hosrc = hkind == 2 ? pold : hsrc;
     const size_t hq = hkind == 0 ? col[0] : hoff;       // plane offset added per plane
-    auto sel = [&](T v) { return first ? T(0) : v; };
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
+        const size_t Q1 = col[e] + nn * wr(k0 + 1);
         wq4[e] = w[col[e] + nn * wr(k0 + 2)];
-        rn1[e] = r[col[e] + nn * wr(k0 + 1)];
-        dn1[e] = diag[col[e] + nn * wr(k0 + 1)];
-        on1[e] = pold[col[e] + nn * wr(k0 + 1)];   // raw; the select is applied at its use
+        rn1[e] = rin[Q1];
+        dn1[e] = diag[Q1];
+        if (UPD) {
+            qn1[e] = qold[Q1];
+            on1[e] = pold[Q1];
+        }
     }
-    T ha = hsrc[nn * (size_t)k0 + hq], hd = diag[nn * (size_t)k0 + hq];
-    T ho = pold[nn * (size_t)k0 + hq];
-    double acc = 0.0;
+    T ha = hsrc[nn * (size_t)k0 + hq], hd = hdsrc[nn * (size_t)k0 + hq];
+    T hqv = UPD ? hqsrc[nn * (size_t)k0 + hq] : T(0), ho = UPD ? hosrc[nn * (size_t)k0 + hq] : T(0);
+    double acc[CG_COLS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int kk = k0; kk < k1; ++kk) {
         const size_t pl = nn * (size_t)kk;
-        T wq4c[RPT], dn[RPT], pp[RPT], on[RPT];
+        T wq4c[RPT], dn[RPT], pp[RPT], on[RPT], rp[RPT], zp[RPT], ip[RPT];
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
             wq4c[e] = wq4[e];
             dn[e] = dn1[e];
-            on[e] = on1[e];
-            pp[e] = rn1[e] / dn1[e] + beta * sel(on1[e]);
+            on[e] = UPD ? on1[e] : T(0);
+            rp[e] = resf(rn1[e], UPD ? qn1[e] : T(0));
+            ip[e] = jinv(dn1[e]);
+            zp[e] = rp[e] * ip[e];
+            pp[e] = dirf(zp[e], on[e]);
         }
-        const T hwc = ha, hpc = ha / hd + beta * sel(ho);
+        T hpc = T(0);
+        if (hkind == 2) hpc = dirf(resf(ha, hqv) * jinv(hd), ho);
+        const T hwc = ha;
         {
             const size_t Hf = nn * (size_t)wr(kk + 1) + hq;
 #pragma unroll
             for (int e = 0; e < RPT; ++e) {
                 const size_t Qf = col[e] + nn * wr(kk + 2);
                 wq4[e] = w[col[e] + nn * wr(kk + 3)];
-                rn1[e] = r[Qf];
+                rn1[e] = rin[Qf];
                 dn1[e] = diag[Qf];
-                on1[e] = pold[Qf];
-                if (XUPD) xn1[e] = x[col[e] + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk)];
+                if (UPD) {
+                    qn1[e] = qold[Qf];
+                    on1[e] = pold[Qf];
+                    xn1[e] = x[col[e] + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk)];
+                }
             }
             ha = hsrc[Hf];
-            hd = diag[Hf];
-            ho = pold[Hf];
+            hd = hdsrc[Hf];
+            if (UPD) {
+                hqv = hqsrc[Hf];
+                ho = hosrc[Hf];
+            }
         }
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
@@ -1097,8 +1158,11 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
             const T qv = (dc[e] - sumK * inv_h2) * c0 + lap * inv_h2;
             q[col[e] + pl] = qv;
             pnew[col[e] + pl] = c0;
-            if (XUPD) x[col[e] + pl] = xnew(xc[e], oc[e]);
-            acc += (double)c0 * (double)qv;
+            if (UPD) {
+                rout[col[e] + pl] = rc[e];
+                x[col[e] + pl] = xnew(xc[e], oc[e]);
+            }
+            cg_accumulate(acc, c0, qv, rc[e], zc[e], ic[e]);
         }
         lds_barrier();
 #pragma unroll
@@ -1109,59 +1173,41 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
             wq3[e] = wq4c[e];
             pm[e] = pc[e];
             pc[e] = pp[e];
+            rc[e] = rp[e];
+            zc[e] = zp[e];
+            ic[e] = ip[e];
             dc[e] = dn[e];
-            if (XUPD) {
+            if (UPD) {
                 oc[e] = on[e];
                 xc[e] = xn1[e];
             }
         }
     }
-    double v[1] = {acc};
-    block_partials<1, 0u>(v, part_s);
+    block_partials<CG_COLS, 0u>(acc, part_out);
 }
 
-// Row form of the first half for n = 64 V: a block of kRowWaves wavefronts
-// owns as many consecutive full x-rows (wavefront v: row j0 + v; lane l:
-// cells x = V l .. V l + V - 1, one vector load per field) and marches along
-// z over cz planes.  A whole periodic row lives in one wavefront, so the
-// x neighbours come from the lane's own cells and one lane rotation and no
-// x halo is read.  y neighbours come from LDS rows (halo 2 for w, 1 for p)
+// Row form for n = 64 V: a block of kRowWaves wavefronts owns as many
+// consecutive full x-rows (wavefront v: row j0 + v; lane l: cells
+// x = V l .. V l + V - 1, one vector load per field) and marches along z over
+// cz planes.  A whole periodic row lives in one wavefront, so the x
+// neighbours come from the lane's own cells and one lane rotation and no x
+// halo is read.  y neighbours come from LDS rows (halo 2 for w, 1 for p)
 // loaded by wavefronts 0-5; z neighbours from per-lane register queues, the
 // lower z face coefficient carried over from the plane below.  Prefetches
 // past the chunk's last needed plane are clamped to planes already read.
-template <typename T, int V, bool XUPD>
+template <typename T, int V, bool UPD>
 __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
-    Phys ph, DevState* st, int k, const T* __restrict__ r, const T* __restrict__ diag,
-    const T* __restrict__ w, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ q,
-    T* __restrict__ x, const double* part_u, unsigned nb_u, double* part_s, int fresh, int maxit,
-    int xzero) {
+    Phys ph, DevState* st, int k, const T* __restrict__ rin, T* __restrict__ rout,
+    const T* __restrict__ diag, const T* __restrict__ w, const T* __restrict__ pold,
+    T* __restrict__ pnew, const T* __restrict__ qold, T* __restrict__ q, T* __restrict__ x,
+    const double* part_in, unsigned nb_in, double* part_out, int fresh, int maxit, int xzero) {
     using VT = T __attribute__((ext_vector_type(V)));
     static_assert(kRowWaves >= 6, "wavefronts 0-5 load the y halo rows");
     MEMBER(ph)
-    // it_stop == k is this launch's own decision, written by the member's
-    // first block: the other blocks must still take the stop path below
-    if (k > (st + mem_)->pcg.it_stop) return;
-    double t[3];
-    reduce_member<3, 0u>(part_u, nb_u, ph.batch, mem_, t);
-    const double rz = t[0], rr = t[1];
-    const bool newb = fresh && k == 0;
-    const double bb = newb ? t[2] : (st + mem_)->pcg.bb;
-    const double tol2 = (st + mem_)->pcg.tol2;
-    const bool conv = rr <= tol2 * bb;
-    const bool stop = conv || k >= maxit;
-    if (MEMBER_FIRST()) {
-        PcgState& g = (st + mem_)->pcg;
-        g.rr = rr;
-        g.iters = k;
-        g.rzh[k & 1] = rz;
-        if (newb) g.bb = bb;
-        if (stop) {
-            g.it_stop = k;
-            g.converged = conv ? 1 : 0;
-        }
-    }
-    const T beta = k == 0 ? T(0) : (T)(rz / (st + mem_)->pcg.rzh[(k - 1) & 1]);
-    const bool first = k == 0;
+    if (k > (st + mem_)->pcg.it_stop) return;   // see k_pcg_spmv
+    const CgHead h = cg_head(ph, (st + mem_)->pcg, MEMBER_FIRST(), mem_, k, part_in, nb_in, fresh,
+                             maxit);
+    const T alpha = (T)h.alpha, beta = (T)h.beta;
     const T inv_h2 = (T)ph.inv_h2;
     const int n = ph.n, cz = ph.cz;   // n == 64 V
     constexpr int TY = kRowWaves;
@@ -1175,60 +1221,83 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
     auto ld = [](const T* f, size_t o) { return *reinterpret_cast<const VT*>(f + o); };
     auto st_v = [](T* f, size_t o, VT v) { *reinterpret_cast<VT*>(f + o) = v; };
-    auto sel = [&](VT v) { return first ? VT(T(0)) : v; };
     const size_t col = base_ + (size_t)n * (j0 + wv) + (size_t)V * lane;
-    // the previous iteration's x update (see k_pcg_spmv)
-    const T alpha = XUPD ? (T)(st + mem_)->pcg.alpha : T(0);
-    const bool xset = XUPD && k == 1 && xzero;
+    const bool xset = UPD && k == 1 && xzero;
     auto xnew = [&](VT xo, VT po) { return xset ? alpha * po : xo + alpha * po; };
-    if (stop) {
-        if (XUPD || xzero) {
+    if (h.stop) {
+        if (UPD || xzero) {
             for (int kk = k0; kk < k1; ++kk) {
                 const size_t Q = col + nn * (size_t)kk;
-                st_v(x, Q, XUPD ? xnew(ld(x, Q), ld(pold, Q)) : VT(T(0)));
+                st_v(x, Q, UPD ? xnew(ld(x, Q), ld(pold, Q)) : VT(T(0)));
             }
         }
         return;
     }
+    // r_k and p_k of a cell from its r_{k-1}, q_{k-1}, diag, p_{k-1}
+    auto resf = [&](VT ro, VT qo) -> VT { return UPD ? ro - alpha * qo : ro; };
+    auto dirf = [&](VT z, VT po) -> VT { return UPD ? z + beta * po : z; };
+    auto ldu = [&](const T* f, size_t o) { return UPD ? ld(f, o) : VT(T(0)); };
     // this wavefront's y halo row: w rows j0-2, j0-1, j0+TY, j0+TY+1 (waves
-    // 0-3), p rows j0-1, j0+TY (waves 4-5, from r, diag and p_old); waves 6..
-    // read their own row so that every load is unconditional
+    // 0-3), p rows j0-1, j0+TY (waves 4-5, from r, q, diag and p_old); waves
+    // 6.. read their own w row so that every load is unconditional.  Waves
+    // other than 4-5 point all four halo loads at the same w row (cache hits).
     const int hrow = wv < 2 ? j0 - 2 + wv : wv < 4 ? j0 + TY - 2 + wv
                    : wv == 4 ? j0 - 1 : wv == 5 ? j0 + TY : j0 + wv;
     const size_t hcol = base_ + (size_t)n * wr(hrow) + (size_t)V * lane;
-    const T* hsrc = wv < 4 ? w : r;
+    const bool phalo = wv == 4 || wv == 5;
+    const T* hsrc = phalo ? rin : w;
+    const T* hdsrc = phalo ? diag : w;
+    const T* hosrc = phalo ? pold : w;
+    const T* hqsrc = phalo ? qold : w;
     auto plane = [&](int kk) { return nn * (size_t)wr(kk); };
     const VT wmm = ld(w, col + plane(k0 - 2));
     VT wm1 = ld(w, col + plane(k0 - 1)), w0 = ld(w, col + plane(k0)), wp1 = ld(w, col + plane(k0 + 1));
     VT wp2n = ld(w, col + plane(k0 + 2));
-    VT pm = ld(r, col + plane(k0 - 1)) / ld(diag, col + plane(k0 - 1)) + beta * sel(ld(pold, col + plane(k0 - 1)));
-    VT oc = ld(pold, col + plane(k0));   // raw p_old of the current plane (x update)
-    VT pc = ld(r, col + plane(k0)) / ld(diag, col + plane(k0)) + beta * sel(oc);
-    VT xc = XUPD ? ld(x, col + plane(k0)) : VT(T(0)), xn1 = xc;
-    VT dc = ld(diag, col + plane(k0));
-    VT rnx = ld(r, col + plane(k0 + 1)), dnx = ld(diag, col + plane(k0 + 1)), onx = ld(pold, col + plane(k0 + 1));
-    VT h1 = ld(hsrc, hcol + plane(k0)), h2 = ld(diag, hcol + plane(k0)), h3 = ld(pold, hcol + plane(k0));
+    const size_t Qm = col + plane(k0 - 1), Q0 = col + plane(k0), Q1 = col + plane(k0 + 1);
+    auto jv = [](VT d) {
+        VT o;
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = jinv(d[i]);
+        return o;
+    };
+    VT pm = dirf(resf(ld(rin, Qm), ldu(qold, Qm)) * jv(ld(diag, Qm)), ldu(pold, Qm));
+    VT oc = ldu(pold, Q0);   // p_old of the current plane (x update)
+    VT dc = ld(diag, Q0);
+    VT rc = resf(ld(rin, Q0), ldu(qold, Q0));
+    VT ic = jv(dc), zc = rc * ic;
+    VT pc = dirf(zc, oc);
+    VT xc = UPD ? ld(x, Q0) : VT(T(0)), xn1 = xc;
+    VT rnx = ld(rin, Q1), qnx = ldu(qold, Q1), dnx = ld(diag, Q1), onx = ldu(pold, Q1);
+    VT h1 = ld(hsrc, hcol + plane(k0)), h2 = ld(hdsrc, hcol + plane(k0));
+    VT h3 = ldu(hosrc, hcol + plane(k0)), h4 = ldu(hqsrc, hcol + plane(k0));
     VT kzm = (T(9) * (wm1 + w0) - (wmm + wp1)) * T(0.0625);
     auto from_left = [&](T v) { return __shfl(v, (lane + 63) & 63, 64); };
     auto from_right = [&](T v) { return __shfl(v, (lane + 1) & 63, 64); };
-    double acc = 0.0;
+    double acc[CG_COLS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int kk = k0; kk < k1; ++kk) {
         const VT wp2 = wp2n;
-        const VT pp = rnx / dnx + beta * sel(onx);
+        const VT rp = resf(rnx, qnx);
+        const VT ip = jv(dnx), zp = rp * ip;
+        const VT pp = dirf(zp, onx);
         const VT dn = dnx, on = onx;
-        const VT hw = h1, hp = h1 / h2 + beta * sel(h3);
+        const VT hw = h1;
+        VT hp = VT(T(0));
+        if (phalo) hp = dirf(resf(h1, h4) * jv(h2), h3);
         {
             const int kw = kk + 3 < k1 + 1 ? kk + 3 : k1 + 1;   // last w plane needed: k1 + 1
             const int kp = kk + 2 < k1 ? kk + 2 : k1;           // last p plane needed: k1
             const int kh = kk + 1 < k1 - 1 ? kk + 1 : k1 - 1;   // last halo plane: k1 - 1
+            const size_t Qp = col + plane(kp), Qh = hcol + plane(kh);
             wp2n = ld(w, col + plane(kw));
-            rnx = ld(r, col + plane(kp));
-            dnx = ld(diag, col + plane(kp));
-            onx = ld(pold, col + plane(kp));
-            h1 = ld(hsrc, hcol + plane(kh));
-            h2 = ld(diag, hcol + plane(kh));
-            h3 = ld(pold, hcol + plane(kh));
-            if (XUPD) xn1 = ld(x, col + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk));
+            rnx = ld(rin, Qp);
+            qnx = ldu(qold, Qp);
+            dnx = ld(diag, Qp);
+            onx = ldu(pold, Qp);
+            h1 = ld(hsrc, Qh);
+            h2 = ld(hdsrc, Qh);
+            h3 = ldu(hosrc, Qh);
+            h4 = ldu(hqsrc, Qh);
+            if (UPD) xn1 = ld(x, col + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk));
         }
         wl[wv + 2][lane] = w0;
         pl[wv + 1][lane] = pc;
@@ -1270,12 +1339,13 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
             const T sumK = kxp + kxm + kyp + kym + kzp[i] + kzm[i];
             const T qv = (dc[i] - sumK * inv_h2) * c0 + lap * inv_h2;
             qo[i] = qv;
-            acc += (double)c0 * (double)qv;
+            cg_accumulate(acc, c0, qv, rc[i], zc[i], ic[i]);
         }
         const size_t pl0 = nn * (size_t)kk;
         st_v(q, col + pl0, qo);
         st_v(pnew, col + pl0, pc);
-        if (XUPD) {
+        if (UPD) {
+            st_v(rout, col + pl0, rc);
             st_v(x, col + pl0, xnew(xc, oc));
             xc = xn1;
             oc = on;
@@ -1286,66 +1356,12 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
         kzm = kzp;
         pm = pc;
         pc = pp;
+        rc = rp;
+        zc = zp;
+        ic = ip;
         dc = dn;
     }
-    double v[1] = {acc};
-    block_partials<1, 0u>(v, part_s);
-}
-
-// Iteration k, second half: alpha_k = r_k.z_k / p_k.q from the previous
-// kernel's partials, r -= alpha q, and partial sums of r.(r/diag) and r.r
-// for the next first half.  x += alpha p is left to that first half (it
-// reads p_k anyway): alpha_k goes to the member state.  The work is
-// pointwise, so the launch is flat: per_member blocks per member (the block
-// count of the stencil launch whose partials the first half also reads),
-// block c of member m streaming one contiguous chunk of its cells, four
-// cells per thread and load when N is a multiple of 4.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_pcg_update(Phys ph, DevState* st, int k,
-                                                       T* __restrict__ r, const T* __restrict__ q,
-                                                       const T* __restrict__ diag,
-                                                       const double* part_s, double* part_u,
-                                                       unsigned nb_s, unsigned per_member) {
-    using V4 = T __attribute__((ext_vector_type(4)));
-    const unsigned id = flat_bid();
-    const int mem_ = (int)(id / per_member);
-    const unsigned chunk = id - (unsigned)mem_ * per_member;
-    if (k >= (st + mem_)->pcg.it_stop) return;
-    double pq[1];
-    reduce_member<1, 0u>(part_s, nb_s, ph.batch, mem_, pq);
-    const double alpha64 = (st + mem_)->pcg.rzh[k & 1] / pq[0];
-    const T alpha = (T)alpha64;
-    if (chunk == 0 && threadIdx.x == 0) (st + mem_)->pcg.alpha = alpha64;
-    const size_t N = ph.N;
-    const size_t C = (((N + per_member - 1) / per_member) + 3) & ~(size_t)3;   // cells per block
-    const size_t beg = (size_t)chunk * C < N ? (size_t)chunk * C : N;
-    const size_t end = beg + C < N ? beg + C : N;
-    const size_t base = (size_t)mem_ * N;
-    double v[3] = {0.0, 0.0, 0.0};
-    auto cell = [&](T rv, T qv, T dv) {
-        const T rn = rv - alpha * qv;
-        v[0] += (double)rn * ((double)rn / (double)dv);
-        v[1] += (double)rn * (double)rn;
-        return rn;
-    };
-    if (N % 4 == 0) {   // beg, end and base are multiples of 4: aligned vectors
-        for (size_t i = beg + 4 * (size_t)threadIdx.x; i < end; i += 4 * (size_t)blockDim.x) {
-            const size_t P = base + i;
-            const V4 rv = *reinterpret_cast<const V4*>(r + P);
-            const V4 qv = *reinterpret_cast<const V4*>(q + P);
-            const V4 dv = *reinterpret_cast<const V4*>(diag + P);
-            V4 rn;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) rn[e] = cell(rv[e], qv[e], dv[e]);
-            *reinterpret_cast<V4*>(r + P) = rn;
-        }
-    } else {
-        for (size_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
-            const size_t P = base + i;
-            r[P] = cell(r[P], q[P], diag[P]);
-        }
-    }
-    block_partials<3, 0u>(v, part_u);
+    block_partials<CG_COLS, 0u>(acc, part_out);
 }
 
 // y = M x for the stand-alone operator entry point (psi/dt given as a field).
@@ -2845,18 +2861,17 @@ unsigned Ops<T>::refine(const Launch& L, const Launch& TL, hipStream_t s, const 
         LAUNCH((k_refine<T, false>), L, s, ph, st, x64, d, x64n, b64, w, diag, r32, part_u);
     return L.nblocks;
 }
-template <typename T, bool XUPD>
+template <typename T, bool UPD>
 static void spmv_launch(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
-                        DevState* st, int k, const T* r, const T* diag, const T* w, const T* pold,
-                        T* pnew, T* q, T* x, const double* part_u, unsigned nb_u, double* part_s,
-                        int fresh, int maxit, int xzero) {
+                        DevState* st, int k, const CgArgs<T>& a) {
+#define SPMV_ARGS st, k, a.rin, a.rout, a.diag, a.w, a.pold, a.pnew, a.qold, a.q, a.x, a.part_in, \
+                  a.nb_in, a.part_out, a.fresh, a.maxit, a.xzero
     if constexpr (sizeof(T) == 4) {
         if (TL.nblocks && TL.v == kRowCells) {
             Phys pt = ph;
             pt.cz = TL.cz;
             pt.nz = TL.nz;
-            LAUNCH((k_pcg_spmv_rows<T, kRowCells, XUPD>), TL, s, pt, st, k, r, diag, w, pold, pnew, q,
-                   x, part_u, nb_u, part_s, fresh, maxit, xzero);
+            LAUNCH((k_pcg_spmv_rows<T, kRowCells, UPD>), TL, s, pt, SPMV_ARGS);
             return;
         }
     }
@@ -2864,33 +2879,19 @@ static void spmv_launch(const Launch& L, const Launch& TL, hipStream_t s, const 
         Phys pt = ph;
         pt.cz = TL.cz;
         pt.nz = TL.nz;
-        LAUNCH((k_pcg_spmv_tiled<T, kSpmvRows, XUPD>), TL, s, pt, st, k, r, diag, w, pold, pnew, q,
-               x, part_u, nb_u, part_s, fresh, maxit, xzero);
+        LAUNCH((k_pcg_spmv_tiled<T, kSpmvRows, UPD>), TL, s, pt, SPMV_ARGS);
     } else {
-        LAUNCH((k_pcg_spmv<T, XUPD>), L, s, ph, st, k, r, diag, w, pold, pnew, q, x, part_u, part_s,
-               nb_u, fresh, maxit, xzero);
+        LAUNCH((k_pcg_spmv<T, UPD>), L, s, ph, SPMV_ARGS);
     }
+#undef SPMV_ARGS
 }
 template <typename T>
-void Ops<T>::pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
-                      DevState* st, int k, const T* r, const T* diag, const T* w, const T* pold,
-                      T* pnew, T* q, T* x, const double* part_u, unsigned nb_u, double* part_s,
-                      int fresh, int maxit, int xzero) {
+void Ops<T>::pcg_iter(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                      DevState* st, int k, const CgArgs<T>& a) {
     if (k == 0)
-        spmv_launch<T, false>(L, TL, s, ph, st, k, r, diag, w, pold, pnew, q, x, part_u, nb_u,
-                              part_s, fresh, maxit, xzero);
+        spmv_launch<T, false>(L, TL, s, ph, st, k, a);
     else
-        spmv_launch<T, true>(L, TL, s, ph, st, k, r, diag, w, pold, pnew, q, x, part_u, nb_u,
-                             part_s, fresh, maxit, xzero);
-}
-template <typename T>
-void Ops<T>::pcg_update(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
-                        DevState* st, int k, T* r, const T* q, const T* diag,
-                        const double* part_s, double* part_u) {
-    // flat launch with the stencil launch's block count and member layout
-    hipLaunchKernelGGL(k_pcg_update<T>, dim3(L.nblocks), dim3(kBlock), 0, s, ph, st, k, r, q, diag,
-                       part_s, part_u, TL.nblocks ? TL.nblocks : L.nblocks,
-                       L.nblocks / (unsigned)ph.batch);
+        spmv_launch<T, true>(L, TL, s, ph, st, k, a);
 }
 template <typename T>
 void Ops<T>::helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt, const T* w,

@@ -46,15 +46,39 @@ constexpr int kSpmvRows = 1;
 constexpr int kRowCells = 4, kRowWaves = 8, kRowBlocks = 256;
 Launch make_spmv_launch(int n, int batch, int elem_bytes);
 
+// Partial-sum columns written by one CG iteration.
+constexpr int kCgCols = 7;
+
 // Partial-sum slots in the workspace (columns of num_blocks doubles each).
 enum PartSlot {
     PS_CFL = 0,    // 1 column: Courant maxima
-    PS_U = 1,      // 3 columns: r.z, r.r, b.b (CG second half / system set-up)
-    PS_S = 4,      // 1 column: p.q (CG first half)
-    PS_MASS = 5,   // 3 columns: sum r, sum |u|^2, max(-rho)
-    PS_STAT = 8,   // 4 columns: statistics
-    PS_DUST = 12,  // kMaxClasses columns: dust class masses
-    PS_COLUMNS = 12 + kMaxClasses
+    PS_U = 1,      // 3 columns: r.z, r.r, b.b (CG system set-up)
+    PS_CG = 4,     // 2 x kCgCols columns: CG iteration k in set k & 1
+    PS_MASS = PS_CG + 2 * kCgCols,   // 3 columns: sum r, sum |u|^2, max(-rho)
+    PS_STAT = PS_MASS + 3,           // 4 columns: statistics
+    PS_DUST = PS_STAT + 4,           // kMaxClasses columns: dust class masses
+    PS_COLUMNS = PS_DUST + kMaxClasses
+};
+
+// Operands of CG iteration k.  Reads r_{k-1}, p_{k-1}, q_{k-1} (rin, pold,
+// qold; only rin = r_0 at k = 0), diag and w; writes r_k (k >= 1), p_k, q_k
+// and updates x.  part_in: the partials of iteration k-1 (kCgCols columns),
+// at k = 0 those of the set-up kernel (r.z, r.r, b.b), written by nb_in
+// blocks; part_out: this iteration's.  fresh: the set-up's b.b is the
+// reference ||b||^2 of the solve; xzero: the solve started from x = 0 without
+// x being written.
+template <typename T>
+struct CgArgs {
+    const T* rin;
+    T* rout;
+    const T *diag, *w, *pold;
+    T* pnew;
+    const T* qold;
+    T *q, *x;
+    const double* part_in;
+    unsigned nb_in;
+    double* part_out;
+    int fresh, maxit, xzero;
 };
 
 template <typename T>
@@ -97,17 +121,10 @@ struct Ops {
                            DevState* st, const double* x64, const T* d, double* x64n,
                            const double* b64, const T* w, const T* diag, T* r32,
                            double* part_u, bool from_zero);
-    // TL: the tiled CG launch of make_spmv_launch (used when TL.nblocks > 0)
-    // k >= 1 also applies the previous iteration's x += alpha p; xzero: the
-    // solve started from x = 0 without x being written; nb_u: the number of
-    // partials in part_u (blocks of the kernel that wrote them)
-    static void pcg_spmv(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
-                         DevState* st, int k, const T* r, const T* diag, const T* w,
-                         const T* pold, T* pnew, T* q, T* x, const double* part_u, unsigned nb_u,
-                         double* part_s, int fresh, int maxit, int xzero);
-    static void pcg_update(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
-                           DevState* st, int k, T* r, const T* q, const T* diag,
-                           const double* part_s, double* part_u);
+    // CG iteration k (one kernel); TL: the CG launch of make_spmv_launch
+    // (used when TL.nblocks > 0)
+    static void pcg_iter(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                         DevState* st, int k, const CgArgs<T>& a);
     static void helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt,
                            const T* w, const T* x, T* y);
     static void helm_start(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,

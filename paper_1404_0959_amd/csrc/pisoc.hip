@@ -61,7 +61,7 @@ std::vector<std::pair<int, int>> shape_candidates(int n) {
 // Byte offsets of every buffer inside the workspace (all members of a batch).
 struct Layout {
     size_t state, partials;
-    size_t rn, rk, aP, divu, pn, w, p0, r, x, diag, pp0, pp1, q, Y0, Y1;
+    size_t rn, rk, aP, divu, pn, w, p0, r, r2, x, diag, pp0, pp1, q, q2, Y0, Y1;
     size_t u3[3], phin, phik, src, hbya, phiH, acc, G;
     size_t rhop, rhop1;
     size_t snap;   // 4 FP64 fields when capturing
@@ -74,12 +74,12 @@ struct Layout {
 // Kernel classes for the optional per-launch event timing.
 enum KCls {
     KC_CFL, KC_PREDICT, KC_MOM_SOURCE, KC_MOM_SWEEP, KC_HBYA, KC_CORR_RHS, KC_PCG_SPMV,
-    KC_PCG_UPDATE, KC_CORR_FLUX, KC_CORR_UPDATE, KC_DUDT, KC_DUST_FLUX, KC_DUST_SWEEP,
+    KC_CORR_FLUX, KC_CORR_UPDATE, KC_DUDT, KC_DUST_FLUX, KC_DUST_SWEEP,
     KC_DUST_FACEFLUX, KC_DUST_FINISH, KC_REFINE, KC_NET, KC_COUNT
 };
 const char* const kKernelName[KC_COUNT] = {
     "k_cfl", "k_predict", "k_mom_source", "k_mom_sweep", "k_hbya", "k_corr_rhs",
-    "k_pcg_spmv", "k_pcg_update", "k_corr_flux", "k_corr_update", "k_dudt", "k_dust_flux",
+    "k_pcg_spmv", "k_corr_flux", "k_corr_update", "k_dudt", "k_dust_flux",
     "k_dust_sweep", "k_dust_faceflux", "k_dust_finish", "k_refine", "learned_guess"};
 
 struct Prof {
@@ -161,8 +161,8 @@ Layout make_layout(const pisoc_params* p, int batch) {
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     L.state = take(sizeof(DevState) * (size_t)batch);
     L.partials = take(sizeof(double) * PS_COLUMNS * (size_t)L.max_blocks);
-    size_t* one[] = {&L.rn, &L.rk, &L.aP, &L.divu, &L.pn, &L.w, &L.p0, &L.r, &L.x, &L.diag,
-                     &L.pp0, &L.pp1, &L.q, &L.Y0, &L.Y1};
+    size_t* one[] = {&L.rn, &L.rk, &L.aP, &L.divu, &L.pn, &L.w, &L.p0, &L.r, &L.r2, &L.x,
+                     &L.diag, &L.pp0, &L.pp1, &L.q, &L.q2, &L.Y0, &L.Y1};
     for (size_t* o : one) *o = take(es * N);
     size_t* three[] = {&L.u3[0], &L.u3[1], &L.u3[2], &L.phin, &L.phik, &L.src, &L.hbya,
                        &L.phiH, &L.acc, &L.G};
@@ -306,55 +306,64 @@ void set_shape(pisoc_ctx* ctx, const Launch& L) {
     ctx->ph.nz = L.nz;
 }
 
-// CG on the system already set up by corr_rhs / helm_start / guess_apply /
-// k_refine (which left the partials r0.z0, r0.r0, b.b), to the tolerance
-// already set in each member's state.  Launches the first half of iteration
-// 0, then (second half k, first half k+1) pairs; the first half of k+1 tests
-// convergence, and every launch after a member's stop returns at once for
-// that member.  eager: pairs in batches, the first sized `pairs`, the host
-// waiting after each until every member has stopped; otherwise exactly
-// `pairs` pairs (capture).  Returns the largest iteration count (eager).
+// The vectors of one CG solve: r_k, p_k and q_k in r[k & 1], p[k & 1],
+// q[k & 1] (the set-up kernel leaves r_0 in r[0]).
 template <typename T>
-pisoc_status run_pcg(pisoc_ctx* ctx, T* r, T* x, T* diag, T* w, T* pp0, T* pp1, T* q, bool fresh,
-                     int pairs, bool eager, int* iters_max, bool xzero, unsigned nb_first) {
+struct CgVecs {
+    T *r[2], *p[2], *q[2];
+    T *x, *diag, *w;
+};
+
+// CG on the system already set up by corr_rhs / helm_start / guess_apply /
+// k_refine (which left r_0 and the partials r0.z0, r0.r0, b.b written by
+// nb_first blocks), to the tolerance already set in each member's state.
+// Launches iterations 0, 1, ...: iteration k tests convergence of r_k, and
+// every launch after a member's stop returns at once for that member.  eager:
+// iterations in batches, the first batch of `iters` after iteration 0, the
+// host waiting after each until every member has stopped; otherwise exactly
+// `iters` after iteration 0 (capture).  Returns the largest iteration count
+// (eager).
+template <typename T>
+pisoc_status run_pcg(pisoc_ctx* ctx, const CgVecs<T>& v, bool fresh, int iters, bool eager,
+                     int* iters_max, bool xzero, unsigned nb_first) {
     using O = Ops<T>;
     const int maxit = ctx->prm.p_maxit;
-    T* pp[2] = {pp0, pp1};
-    double* pu = ctx->part(PS_U);
-    double* ps = ctx->part(PS_S);
-    auto spmv = [&](int k) {
-        // words: r, diag, w read, p, q written; from k = 1 also p_old read and x updated
-        timed(ctx, KC_PCG_SPMV, k == 0 ? 5.0 : 8.0, k, [&] {
-            // the start's partials come from the set-up kernel, later ones from k_pcg_update
-            O::pcg_spmv(ctx->L, ctx->TS, ctx->stream, ctx->ph, ctx->st, k, r, diag, w,
-                        pp[(k + 1) & 1], pp[k & 1], q, x, pu, k == 0 ? nb_first : ctx->L.nblocks,
-                        ps, fresh ? 1 : 0, maxit, xzero ? 1 : 0);
+    const unsigned nb_cg = ctx->TS.nblocks ? ctx->TS.nblocks : ctx->L.nblocks;
+    auto iter = [&](int k) {
+        // words: r, diag, w read, p, q written; from k = 1 also q, p_old read, r written and
+        // x updated
+        timed(ctx, KC_PCG_SPMV, k == 0 ? 5.0 : 10.0, k, [&] {
+            CgArgs<T> a;
+            a.rin = v.r[k == 0 ? 0 : (k + 1) & 1];
+            a.rout = v.r[k & 1];
+            a.diag = v.diag;
+            a.w = v.w;
+            a.pold = v.p[(k + 1) & 1];
+            a.pnew = v.p[k & 1];
+            a.qold = v.q[(k + 1) & 1];
+            a.q = v.q[k & 1];
+            a.x = v.x;
+            a.part_in = k == 0 ? ctx->part(PS_U) : ctx->part(PS_CG + kCgCols * ((k + 1) & 1));
+            a.nb_in = k == 0 ? nb_first : nb_cg;
+            a.part_out = ctx->part(PS_CG + kCgCols * (k & 1));
+            a.fresh = fresh ? 1 : 0;
+            a.maxit = maxit;
+            a.xzero = xzero ? 1 : 0;
+            O::pcg_iter(ctx->L, ctx->TS, ctx->stream, ctx->ph, ctx->st, k, a);
         });
     };
-    auto update = [&](int k) {
-        // words: r, q, diag read, r written
-        timed(ctx, KC_PCG_UPDATE, 4.0, k, [&] {
-            O::pcg_update(ctx->L, ctx->TS, ctx->stream, ctx->ph, ctx->st, k, r, q, diag, ps, pu);
-        });
-    };
-    spmv(0);
-    int k = 0;  // first halves launched: 0..k
+    iter(0);
+    int k = 0;  // iterations launched: 0..k
     if (!eager) {
-        const int cap = std::min(std::max(1, pairs), maxit);
-        for (; k < cap; ++k) {
-            update(k);
-            spmv(k + 1);
-        }
+        const int cap = std::min(std::max(1, iters), maxit);
+        for (; k < cap; ++k) iter(k + 1);
         return PISOC_OK;
     }
-    int batch = std::max(1, pairs);
+    int batch = std::max(1, iters);
     int most = 0;
     for (;;) {
         const int kend = std::min(k + batch, maxit);
-        for (; k < kend; ++k) {
-            update(k);
-            spmv(k + 1);
-        }
+        for (; k < kend; ++k) iter(k + 1);
         pisoc_status s = sync_state(ctx);
         if (s != PISOC_OK) return s;
         bool all = true, bad_dt = false;
@@ -407,7 +416,7 @@ void learned_guess(pisoc_ctx* ctx, T* r, T* x, T* dg, T* w, T* p0, T* gbuf, T* m
 template <typename T>
 struct StepPtrs {
     T *rn, *rk, *un, *ua, *ub, *phin, *phik;
-    T *aP, *divu, *pn, *src, *hb, *w, *p0, *phiH, *r, *x, *dg, *pp0, *pp1, *q;
+    T *aP, *divu, *pn, *src, *hb, *w, *p0, *phiH, *r, *r2, *x, *dg, *pp0, *pp1, *q, *q2;
     T *acc, *G, *Ya, *Yb, *rj, *rj1;
     double *snap, *b64, *x64a, *x64b;
 };
@@ -433,11 +442,13 @@ StepPtrs<T> step_ptrs(const pisoc_ctx* ctx) {
     P.p0 = F(Y.p0);
     P.phiH = F(Y.phiH);
     P.r = F(Y.r);
+    P.r2 = F(Y.r2);
     P.x = F(Y.x);
     P.dg = F(Y.diag);
     P.pp0 = F(Y.pp0);
     P.pp1 = F(Y.pp1);
     P.q = F(Y.q);
+    P.q2 = F(Y.q2);
     P.acc = F(Y.acc);
     P.G = F(Y.G);
     P.Ya = F(Y.Y0);
@@ -450,6 +461,21 @@ StepPtrs<T> step_ptrs(const pisoc_ctx* ctx) {
     P.x64a = f32 ? ctx->f<double>(Y.x64a) : nullptr;
     P.x64b = f32 ? ctx->f<double>(Y.x64b) : nullptr;
     return P;
+}
+
+template <typename T>
+CgVecs<T> cg_vecs(const StepPtrs<T>& S) {
+    CgVecs<T> v;
+    v.r[0] = S.r;
+    v.r[1] = S.r2;
+    v.p[0] = S.pp0;
+    v.p[1] = S.pp1;
+    v.q[0] = S.q;
+    v.q[1] = S.q2;
+    v.x = S.x;
+    v.diag = S.dg;
+    v.w = S.w;
+    return v;
 }
 
 // dt, density predictor, momentum source and predictor sweeps (u* ends in
@@ -602,7 +628,7 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
     set_tol(s, ctx->st, B, tau0 * tau0);
     int most = 0;
     const int pairs0 = eager ? (ctx->pred_first[corr] > 0 ? ctx->pred_first[corr] : 8) : ctx->caps[corr];
-    if ((*err = run_pcg<float>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, true, pairs0, eager,
+    if ((*err = run_pcg<float>(ctx, cg_vecs(S), true, pairs0, eager,
                                &most, !guess, ctx->nb_start)) != PISOC_OK)
         return;
     if (eager) ctx->pred_first[corr] = most;
@@ -634,7 +660,7 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
         set_tol_refine(s, ctx->st, B, p.inner_tol);
         // the inner correction of this round starts from zero (not written)
         const int pairs = eager ? std::max(2, ctx->pred_later) : ctx->cap_later;
-        if ((*err = run_pcg<float>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, false, pairs, eager,
+        if ((*err = run_pcg<float>(ctx, cg_vecs(S), false, pairs, eager,
                                    &most, true, nb_ref)) != PISOC_OK)
             return;
         if (eager) ctx->pred_later = most;
@@ -710,7 +736,7 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
             int most = 0;
             const int pairs =
                 eager ? (ctx->pred_first[corr] > 0 ? ctx->pred_first[corr] : 8) : ctx->caps[corr];
-            err = run_pcg<T>(ctx, S.r, S.x, S.dg, S.w, S.pp0, S.pp1, S.q, true, pairs, eager, &most,
+            err = run_pcg<T>(ctx, cg_vecs(S), true, pairs, eager, &most,
                              !guess, ctx->nb_start);
             if (eager) ctx->pred_first[corr] = most;
             record_solve(s, ctx->st, ctx->batch, corr, /*round=*/0, /*add=*/1, /*fin=*/1);
@@ -1151,13 +1177,9 @@ void enqueue_probe(pisoc_ctx* ctx) {
     O::hbya(L, ctx->TL, s, ph, st, S.ua, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0);
     const unsigned nb0 = O::corr_rhs(L, ctx->TL, s, ph, st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH,
                                      S.r, S.dg, ctx->part(PS_U), nullptr, nullptr, nullptr, S.b64);
-    // two CG iterations that cannot stop early (tolerance 0, maxit above 2)
+    // two CG iterations that cannot converge (tolerance 0)
     set_tol(s, st, ctx->batch, 0.0);
-    for (int k = 0; k < 2; ++k) {
-        O::pcg_spmv(L, ctx->TS, s, ph, st, k, S.r, S.dg, S.w, k ? S.pp0 : S.pp1, k ? S.pp1 : S.pp0,
-                    S.q, S.x, ctx->part(PS_U), k ? L.nblocks : nb0, ctx->part(PS_S), 1, 1 << 20, 1);
-        O::pcg_update(L, ctx->TS, s, ph, st, k, S.r, S.q, S.dg, ctx->part(PS_S), ctx->part(PS_U));
-    }
+    (void)run_pcg<T>(ctx, cg_vecs(S), true, 1, false, nullptr, true, nb0);
     if (ctx->prm.n_classes > 0) O::dust_sweep(L, ctx->TL, s, ph, st, S.Ya, S.Yb, S.G, S.rj, S.rk);
 }
 
@@ -1759,10 +1781,12 @@ static Layout helm_layout(int32_t n) {
     L.state = take(sizeof(DevState));
     L.partials = take(sizeof(double) * PS_COLUMNS * (size_t)L.max_blocks);
     L.r = take(8 * N);
+    L.r2 = take(8 * N);
     L.diag = take(8 * N);
     L.pp0 = take(8 * N);
     L.pp1 = take(8 * N);
     L.q = take(8 * N);
+    L.q2 = take(8 * N);
     L.total = off;
     return L;
 }
@@ -1836,9 +1860,17 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
         double* dg = ctx.f<double>(lay.diag);
         Ops<double>::helm_start(ctx.L, ctx.stream, ctx.ph, ctx.st, d_psidt, d_w, d_b, d_x, r, dg,
                                 ctx.part(PS_U));
-        st = run_pcg<double>(&ctx, r, d_x, dg, const_cast<double*>(d_w), ctx.f<double>(lay.pp0),
-                             ctx.f<double>(lay.pp1), ctx.f<double>(lay.q), true, 16, true, nullptr,
-                             false, ctx.L.nblocks);
+        CgVecs<double> v;
+        v.r[0] = r;
+        v.r[1] = ctx.f<double>(lay.r2);
+        v.p[0] = ctx.f<double>(lay.pp0);
+        v.p[1] = ctx.f<double>(lay.pp1);
+        v.q[0] = ctx.f<double>(lay.q);
+        v.q[1] = ctx.f<double>(lay.q2);
+        v.x = d_x;
+        v.diag = dg;
+        v.w = const_cast<double*>(d_w);
+        st = run_pcg<double>(&ctx, v, true, 16, true, nullptr, false, ctx.L.nblocks);
         if (st == PISOC_OK) {
             const PcgState& g = ctx.hst->pcg;
             if (iters) *iters = g.iters;
