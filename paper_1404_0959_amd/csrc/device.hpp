@@ -222,6 +222,11 @@ __device__ inline BlockXYZ block_xyz() {
             (int)(L / (gridDim.x * gridDim.y))};
 }
 
+// Store that streams past the caches: the written line does not displace
+// lines still to be read (a z-march's halo rows and planes) from L2.
+template <typename T>
+__device__ inline void stream_st(T* p, T v) { __builtin_nontemporal_store(v, p); }
+
 // Barrier that orders only LDS accesses across the block: it waits for this
 // wave's LDS operations, not for its global loads in flight, so loads issued
 // for a later plane of a z-march stay in flight across it (a plain

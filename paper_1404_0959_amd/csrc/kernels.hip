@@ -452,10 +452,11 @@ __global__ void __launch_bounds__(kTX * kTY, sizeof(T) == 4 ? 4 : 2) k_mom_sweep
         T out[3], ia;
         mom_cell<T, HBYA>(u, pv, fp, fm, cs, ca, inv_V, inv_h, mu_h2, out, ia);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) uout[(size_t)m * N + col + pl] = out[m];
+        for (int m = 0; m < 3; ++m) stream_st(uout + ((size_t)m * N + col + pl), out[m]);
         if (HBYA) {
-            w[col + pl] = ((T)(st + mem_)->rho_ref + crk) * ia;
-            p0[col + pl] = pdev(crk, (st + mem_)->rho_ref, (st + mem_)->p_ref, ph.gamma);
+            stream_st(w + (col + pl), ((T)(st + mem_)->rho_ref + crk) * ia);
+            stream_st(p0 + (col + pl),
+                      pdev(crk, (st + mem_)->rho_ref, (st + mem_)->p_ref, ph.gamma));
         }
         lds_barrier();
         // advance the queues with the values loaded one plane ago, then load
@@ -536,15 +537,15 @@ __device__ inline void corr_rhs_store(size_t P, size_t N, double b, T dgT, const
                                       T* __restrict__ diag, double* snap_b, double* snap_diag,
                                       double* snap_p0, double* b64, double (&v)[3]) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) phiH[d * N + P] = phf[d];
+    for (int d = 0; d < 3; ++d) stream_st(phiH + (d * N + P), phf[d]);
     const T bT = (T)b;
-    rvec[P] = bT;
-    diag[P] = dgT;
+    stream_st(rvec + P, bT);
+    stream_st(diag + P, dgT);
     const double bd = (double)bT;
     v[0] += bd * (bd / (double)dgT);
     v[1] += b64 ? b * b : bd * bd;
     v[2] += b64 ? b * b : bd * bd;
-    if (b64) b64[P] = b;
+    if (b64) stream_st(b64 + P, b);
     if (snap_b) {
         snap_b[P] = b;
         snap_diag[P] = (double)dgT;
@@ -1156,11 +1157,11 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
                           kzp * (c0 - pp[e]) + kzm * (c0 - pm[e]);
             const T sumK = kxp + kxm + kyp + kym + kzp + kzm;
             const T qv = (dc[e] - sumK * inv_h2) * c0 + lap * inv_h2;
-            q[col[e] + pl] = qv;
-            pnew[col[e] + pl] = c0;
+            stream_st(q + (col[e] + pl), qv);
+            stream_st(pnew + (col[e] + pl), c0);
             if (UPD) {
-                rout[col[e] + pl] = rc[e];
-                x[col[e] + pl] = xnew(xc[e], oc[e]);
+                stream_st(rout + (col[e] + pl), rc[e]);
+                stream_st(x + (col[e] + pl), xnew(xc[e], oc[e]));
             }
             cg_accumulate(acc, c0, qv, rc[e], zc[e], ic[e]);
         }
@@ -1220,7 +1221,12 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     __shared__ VT pl[TY + 2][64];   // p of rows j0 - 1 .. j0 + TY
     auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
     auto ld = [](const T* f, size_t o) { return *reinterpret_cast<const VT*>(f + o); };
-    auto st_v = [](T* f, size_t o, VT v) { *reinterpret_cast<VT*>(f + o) = v; };
+    // outputs and x stream past the caches (stream_st), keeping L2 for the
+    // halo rows and planes still to be read
+    auto st_v = [](T* f, size_t o, VT v) { stream_st(reinterpret_cast<VT*>(f + o), v); };
+    auto ld_x = [](const T* f, size_t o) {
+        return __builtin_nontemporal_load(reinterpret_cast<const VT*>(f + o));
+    };
     const size_t col = base_ + (size_t)n * (j0 + wv) + (size_t)V * lane;
     const bool xset = UPD && k == 1 && xzero;
     auto xnew = [&](VT xo, VT po) { return xset ? alpha * po : xo + alpha * po; };
@@ -1297,7 +1303,7 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
             h2 = ld(hdsrc, Qh);
             h3 = ldu(hosrc, Qh);
             h4 = ldu(hqsrc, Qh);
-            if (UPD) xn1 = ld(x, col + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk));
+            if (UPD) xn1 = ld_x(x, col + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk));
         }
         wl[wv + 2][lane] = w0;
         pl[wv + 1][lane] = pc;
@@ -2069,7 +2075,8 @@ Launch make_launch_shaped(int n, int batch, int bx, int cz) {
 // halo value is loaded together with its owner tile's queue head of the same
 // plane (four planes ahead, then held in a three-plane register queue), so
 // that the two reads of a line fall together in L2.  Loads past the chunk's
-// last needed plane are clamped to planes already read.
+// last needed plane are clamped to planes already read.  The functors write
+// their outputs with streaming stores (stream_st), as do the other z-marches.
 template <typename T, class K>
 __global__ void __launch_bounds__(kTX * kTY) k_tiled(Phys ph, DevState* st, K kern) {
     MEMBER(ph)
@@ -2300,7 +2307,7 @@ struct TiledMomSource : TiledBase<T> {
         T out[3];
         mom_source_cell(v[0], p.u, rref + p.rn, dt, m3, inv_h, out);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) src[m * this->NT + P] = out[m];
+        for (int m = 0; m < 3; ++m) stream_st(src + (m * this->NT + P), out[m]);
     }
 };
 
@@ -2331,9 +2338,9 @@ struct TiledCorrFlux : TiledBase<T> {
         }
         T pP, fk[3];
         corr_flux_cell(v[0], v[1][0], v[2][0], p0n, xn, p.h, A, inv_h, pP, fk);
-        pt[P] = pP;
+        stream_st(pt + P, pP);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) phik[d * this->NT + P] = fk[d];
+        for (int d = 0; d < 3; ++d) stream_st(phik + (d * this->NT + P), fk[d]);
         if (snap_x) snap_x[P] = (double)v[2][0];
     }
 };
@@ -2371,11 +2378,11 @@ struct TiledCorrUpdate : TiledBase<T> {
                          const Pts& p, double* acc) const {
         T r, um[3];
         corr_update_cell(v[0], fp, fm, p.hb, p.rn, p.a, dt, inv_V, inv_h, r, um);
-        rk[P] = r;
+        stream_st(rk + P, r);
         double usq = 0.0;
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            u[m * this->NT + P] = um[m];
+            stream_st(u + (m * this->NT + P), um[m]);
             usq += (double)um[m] * (double)um[m];
         }
         if (LAST) {
@@ -2408,9 +2415,9 @@ struct TiledRefineFromZero : TiledBase<T> {
         cross7(v[1], dv);
         double xP, r;
         refine_cell(v[0], xv, dv, p.b, p.dg, inv_h2, xP, r);
-        x64n[P] = xP;
+        stream_st(x64n + P, xP);
         const T rT = (T)r;
-        r32[P] = rT;
+        stream_st(r32 + P, rT);
         acc[0] += (double)rT * ((double)rT / (double)p.dg);
         acc[1] += r * r;
         acc[2] += r * r;
@@ -2443,7 +2450,7 @@ struct TiledDudt : TiledBase<T> {
         T out[3];
         dudt_cell(v, p.u0, dt, inv_h, out);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) acc_out[m * this->NT + P] = out[m];
+        for (int m = 0; m < 3; ++m) stream_st(acc_out + (m * this->NT + P), out[m]);
     }
 };
 
@@ -2473,8 +2480,8 @@ struct TiledDustFlux : TiledBase<T> {
         T g[3], y;
         dust_flux_cell(v[0], al, p.f, p.rj, p.rn, t, rref, A, g, y);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) G[d * this->NT + P] = g[d];
-        Y[P] = y;
+        for (int d = 0; d < 3; ++d) stream_st(G + (d * this->NT + P), g[d]);
+        stream_st(Y + P, y);
     }
 };
 
@@ -2495,7 +2502,7 @@ struct TiledDustSweep : TiledBase<T> {
     __device__ Pts load(size_t P) const { return {rhoj[P], r1[P]}; }
     __device__ void cell(size_t P, const T (&v)[1][13], const T (&fp)[3], const T (&fm)[3],
                          const Pts& p, double*) const {
-        Yout[P] = dust_sweep_cell(v[0], fp, fm, p.rj, p.r1, dt, inv_V, rref);
+        stream_st(Yout + P, dust_sweep_cell(v[0], fp, fm, p.rj, p.r1, dt, inv_V, rref));
     }
 };
 
@@ -2525,7 +2532,7 @@ struct TiledDustFinish : TiledBase<T> {
 #pragma unroll
         for (int d = 0; d < 3; ++d) dF += fp[d] * i4g(v[0], d, 0) - fm[d] * i4g(v[0], d, -1);
         const T out = p.rj - dt * dF * inv_V;
-        rhoj1[P] = out;
+        stream_st(rhoj1 + P, out);
         acc[0] += (double)out;
     }
 };
@@ -2577,16 +2584,16 @@ struct TiledCorrFluxUpdate : TiledBase<T> {
         for (int d = 0; d < 3; ++d) {
             fp[d] = hp[d] - i4g(v[0], d, 0) * A * (pv[3 + 4 * d] - pP) * inv_h;
             fm[d] = hm[d] - i4g(v[0], d, -1) * A * (pP - pv[2 + 4 * d]) * inv_h;
-            phik[d * this->NT + P] = fp[d];
+            stream_st(phik + (d * this->NT + P), fp[d]);
         }
         if (snap_x) snap_x[P] = (double)v[2][0];
         T r, um[3];
         corr_update_cell(pv, fp, fm, p.hb, p.rn, p.a, dt, inv_V, inv_h, r, um);
-        rk[P] = r;
+        stream_st(rk + P, r);
         double usq = 0.0;
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            u[m * this->NT + P] = um[m];
+            stream_st(u + (m * this->NT + P), um[m]);
             usq += (double)um[m] * (double)um[m];
         }
         if (LAST) {
@@ -2635,10 +2642,10 @@ struct TiledPredict : TiledBase<T> {
         for (int d = 0; d < 3; ++d) cross_line(v[d], d, ul[d]);
         T r, a, dv, pp;
         predict_cell(fp, fm, ul, p.rn, dt, inv_V, inv_h, diag_visc, rref, pref, gamma, r, a, dv, pp);
-        rs[P] = r;
-        aP[P] = a;
-        divu[P] = dv;
-        pn[P] = pp;
+        stream_st(rs + P, r);
+        stream_st(aP + P, a);
+        stream_st(divu + P, dv);
+        stream_st(pn + P, pp);
     }
     __device__ void first(DevState* d) const {
         if (!(dtd > 0.0) || !isfinite(dtd)) d->flags |= 16;  // bad dt
