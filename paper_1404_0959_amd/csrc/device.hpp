@@ -227,6 +227,11 @@ __device__ inline BlockXYZ block_xyz() {
 template <typename T>
 __device__ inline void stream_st(T* p, T v) { __builtin_nontemporal_store(v, p); }
 
+// Load of a value no other tile reads (a z-march's own point values), with
+// the same streaming hint.
+template <typename T>
+__device__ inline T stream_ld(const T* p) { return __builtin_nontemporal_load(p); }
+
 // Barrier that orders only LDS accesses across the block: it waits for this
 // wave's LDS operations, not for its global loads in flight, so loads issued
 // for a later plane of a z-march stay in flight across it (a plain

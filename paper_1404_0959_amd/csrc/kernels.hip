@@ -390,10 +390,10 @@ __global__ void __launch_bounds__(kTX * kTY, sizeof(T) == 4 ? 4 : 2) k_mom_sweep
         nfz = phi[2 * N + col + pv];
         nfx = phi[col + pv];
         nfy = phi[N + col + pv];
-        na = aP[col + pv];
+        na = stream_ld(aP + col + pv);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) ns[m] = s[(size_t)m * N + col + pv];
-        if (HBYA) nrk = rk[col + pv];
+        for (int m = 0; m < 3; ++m) ns[m] = stream_ld(s + (size_t)m * N + col + pv);
+        if (HBYA) nrk = stream_ld(rk + col + pv);
 #pragma unroll
         for (int q = 0; q < kPer; ++q) nh[q] = hsrc[q][phh + hoff[q]];
     };
@@ -676,7 +676,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_corr_rhs_tiled(
         np = p0[col + p3];
         nx = hbya[col + pv];
         ny = hbya[N + col + pv];
-        nrn = rn[col + pv];
+        nrn = stream_ld(rn + col + pv);
 #pragma unroll
         for (int q = 0; q < kPer; ++q) nh[q] = hsrc[q][pv + hoff[q]];
     };
@@ -1120,7 +1120,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
                 if (UPD) {
                     qn1[e] = qold[Qf];
                     on1[e] = pold[Qf];
-                    xn1[e] = x[col[e] + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk)];
+                    xn1[e] = stream_ld(x + col[e] + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk));
                 }
             }
             ha = hsrc[Hf];
@@ -2075,8 +2075,9 @@ Launch make_launch_shaped(int n, int batch, int bx, int cz) {
 // halo value is loaded together with its owner tile's queue head of the same
 // plane (four planes ahead, then held in a three-plane register queue), so
 // that the two reads of a line fall together in L2.  Loads past the chunk's
-// last needed plane are clamped to planes already read.  The functors write
-// their outputs with streaming stores (stream_st), as do the other z-marches.
+// last needed plane are clamped to planes already read.  The functors read
+// their point values with streaming loads (stream_ld) and write their outputs
+// with streaming stores (stream_st), as do the other z-marches.
 template <typename T, class K>
 __global__ void __launch_bounds__(kTX * kTY) k_tiled(Phys ph, DevState* st, K kern) {
     MEMBER(ph)
@@ -2300,7 +2301,9 @@ struct TiledMomSource : TiledBase<T> {
         rref = (T)d->rho_ref;
     }
     __device__ Pts load(size_t P) const {
-        return {rn[P], {un[P], un[this->NT + P], un[2 * this->NT + P]}};
+        return {stream_ld(rn + P),
+                {stream_ld(un + P), stream_ld(un + this->NT + P),
+                 stream_ld(un + 2 * this->NT + P)}};
     }
     __device__ void cell(size_t P, const T (&v)[1][13], const T (&)[3], const T (&)[3],
                          const Pts& p, double*) const {
@@ -2326,7 +2329,8 @@ struct TiledCorrFlux : TiledBase<T> {
         inv_h = (T)ph.inv_h;
     }
     __device__ Pts load(size_t P) const {
-        return {{phiH[P], phiH[this->NT + P], phiH[2 * this->NT + P]}};
+        return {{stream_ld(phiH + P), stream_ld(phiH + this->NT + P),
+                 stream_ld(phiH + 2 * this->NT + P)}};
     }
     __device__ void cell(size_t P, const T (&v)[3][13], const T (&)[3], const T (&)[3],
                          const Pts& p, double*) const {
@@ -2372,7 +2376,9 @@ struct TiledCorrUpdate : TiledBase<T> {
         }
     }
     __device__ Pts load(size_t P) const {
-        return {{hbya[P], hbya[this->NT + P], hbya[2 * this->NT + P]}, rn[P], aP[P]};
+        return {{stream_ld(hbya + P), stream_ld(hbya + this->NT + P),
+                 stream_ld(hbya + 2 * this->NT + P)},
+                stream_ld(rn + P), stream_ld(aP + P)};
     }
     __device__ void cell(size_t P, const T (&v)[1][13], const T (&fp)[3], const T (&fm)[3],
                          const Pts& p, double* acc) const {
@@ -2407,7 +2413,7 @@ struct TiledRefineFromZero : TiledBase<T> {
     struct Pts { double b; T dg; };
     __device__ void member(const Phys& ph, const DevState*) { inv_h2 = ph.inv_h2; }
     __device__ void init(double* acc) const { acc[0] = acc[1] = acc[2] = 0.0; }
-    __device__ Pts load(size_t P) const { return {b64[P], diag[P]}; }
+    __device__ Pts load(size_t P) const { return {stream_ld(b64 + P), stream_ld(diag + P)}; }
     __device__ void cell(size_t P, const T (&v)[2][13], const T (&)[3], const T (&)[3],
                          const Pts& p, double* acc) const {
         const double xv[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -2443,7 +2449,7 @@ struct TiledDudt : TiledBase<T> {
         inv_h = (T)ph.inv_h;
     }
     __device__ Pts load(size_t P) const {
-        return {{un[P], un[this->NT + P], un[2 * this->NT + P]}};
+        return {{stream_ld(un + P), stream_ld(un + this->NT + P), stream_ld(un + 2 * this->NT + P)}};
     }
     __device__ void cell(size_t P, const T (&v)[3][13], const T (&)[3], const T (&)[3],
                          const Pts& p, double*) const {
@@ -2470,7 +2476,9 @@ struct TiledDustFlux : TiledBase<T> {
         rref = (T)d->rho_ref;
     }
     __device__ Pts load(size_t P) const {
-        return {{phi[P], phi[this->NT + P], phi[2 * this->NT + P]}, rhoj[P], rn[P]};
+        return {{stream_ld(phi + P), stream_ld(phi + this->NT + P),
+                 stream_ld(phi + 2 * this->NT + P)},
+                stream_ld(rhoj + P), stream_ld(rn + P)};
     }
     __device__ void cell(size_t P, const T (&v)[4][13], const T (&)[3], const T (&)[3],
                          const Pts& p, double*) const {
@@ -2499,7 +2507,7 @@ struct TiledDustSweep : TiledBase<T> {
         inv_V = (T)ph.inv_V;
         rref = (T)d->rho_ref;
     }
-    __device__ Pts load(size_t P) const { return {rhoj[P], r1[P]}; }
+    __device__ Pts load(size_t P) const { return {stream_ld(rhoj + P), stream_ld(r1 + P)}; }
     __device__ void cell(size_t P, const T (&v)[1][13], const T (&fp)[3], const T (&fm)[3],
                          const Pts& p, double*) const {
         stream_st(Yout + P, dust_sweep_cell(v[0], fp, fm, p.rj, p.r1, dt, inv_V, rref));
@@ -2525,7 +2533,7 @@ struct TiledDustFinish : TiledBase<T> {
         dt = (T)d->dt;
         inv_V = (T)ph.inv_V;
     }
-    __device__ Pts load(size_t P) const { return {rhoj[P]}; }
+    __device__ Pts load(size_t P) const { return {stream_ld(rhoj + P)}; }
     __device__ void cell(size_t P, const T (&v)[1][13], const T (&fp)[3], const T (&fm)[3],
                          const Pts& p, double* acc) const {
         T dF = T(0);
@@ -2571,7 +2579,9 @@ struct TiledCorrFluxUpdate : TiledBase<T> {
         }
     }
     __device__ Pts load(size_t P) const {
-        return {{hbya[P], hbya[this->NT + P], hbya[2 * this->NT + P]}, rn[P], aP[P]};
+        return {{stream_ld(hbya + P), stream_ld(hbya + this->NT + P),
+                 stream_ld(hbya + 2 * this->NT + P)},
+                stream_ld(rn + P), stream_ld(aP + P)};
     }
     __device__ void cell(size_t P, const T (&v)[3][13], const T (&hp)[3], const T (&hm)[3],
                          const Pts& p, double* acc) const {
@@ -2634,7 +2644,7 @@ struct TiledPredict : TiledBase<T> {
         pref = d->p_ref;
         gamma = ph.gamma;
     }
-    __device__ Pts load(size_t P) const { return {rn[P]}; }
+    __device__ Pts load(size_t P) const { return {stream_ld(rn + P)}; }
     __device__ void cell(size_t P, const T (&v)[3][13], const T (&fp)[3], const T (&fm)[3],
                          const Pts& p, double*) const {
         T ul[3][5];
