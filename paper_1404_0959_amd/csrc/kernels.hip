@@ -76,8 +76,18 @@ __global__ void __launch_bounds__(kBlock) k_init_phi(Phys ph, const DevState* st
 }
 
 // ---------------------------------------------------------------- time step
-// Per-block maxima of the convective Courant rate
-// sigma_P = sum_f |phi_f| / (2 rho_P V); the next kernel turns them into dt.
+// Convective Courant rate sigma_P = sum_f |phi_f| / (2 rho_P V) of a cell
+// from its own (fp) and lower (fm) face fluxes and its density deviation r.
+template <typename T>
+__device__ inline double courant_rate(const T (&fp)[3], const T (&fm)[3], T r, double rref,
+                                      double V) {
+    double f = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) f += fabs((double)fp[d]) + fabs((double)fm[d]);
+    return f / (2.0 * (rref + (double)r) * V);
+}
+
+// Per-block maxima of the Courant rate; the next kernel turns them into dt.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_cfl(Phys ph, const DevState* st, const T* __restrict__ r,
                                                 const T* __restrict__ phi, double* part) {
@@ -93,10 +103,7 @@ __global__ void __launch_bounds__(kBlock) k_cfl(Phys ph, const DevState* st, con
     }
     const T rP = r[P];
     loads_issued();
-    double f = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) f += fabs((double)fp[d]) + fabs((double)fm[d]);
-    double s = f / (2.0 * ((st + mem_)->rho_ref + (double)rP) * ph.V);
+    const double s = courant_rate(fp, fm, rP, (st + mem_)->rho_ref, ph.V);
     v[0] = s > v[0] ? s : v[0];
     END_CELLS
     block_partials<1, 1u>(v, part);
@@ -2549,19 +2556,22 @@ struct TiledDustFinish : TiledBase<T> {
 // 13-point cross, the corrected fluxes phi = phiH - K A snGrad(p) on the
 // cell's own faces (stored) and on its lower faces (from the low-side phiH
 // and the same w and p cells: bitwise the values the neighbours store), then
-// the update of rho_k and u as k_corr_update.  p itself is not stored.
+// the update of rho_k and u as k_corr_update.  p itself is not stored.  LAST
+// (the step's last corrector): the mass-budget partials and, as a fourth
+// column, the Courant maxima of the new state, bitwise what k_cfl computes
+// from it at the start of the next step.
 template <typename T, bool LAST>
 struct TiledCorrFluxUpdate : TiledBase<T> {
     static constexpr int NS = 3;          // w, p0, p'
     static constexpr bool FACES = true;   // phiH
-    static constexpr int NR = LAST ? 3 : 0;
-    static constexpr unsigned MASK = 4u;
+    static constexpr int NR = LAST ? 4 : 0;
+    static constexpr unsigned MASK = 4u | 8u;
     const T* sf[3];
     const T *rn, *hbya, *aP;
     T *phik, *rk, *u;
     double* snap_x;
     T A, inv_h, dt, inv_V;
-    double rref;
+    double rref, V;
     struct Pts { T hb[3], rn, a; };
     __device__ void member(const Phys& ph, const DevState* d) {
         this->NT = ph.NT;
@@ -2570,12 +2580,14 @@ struct TiledCorrFluxUpdate : TiledBase<T> {
         dt = (T)d->dt;
         inv_V = (T)ph.inv_V;
         rref = d->rho_ref;
+        V = ph.V;
     }
     __device__ void init(double* acc) const {
         acc[0] = 0.0;
         if (LAST) {
             acc[1] = 0.0;
             acc[2] = -__builtin_inf();
+            acc[3] = 0.0;
         }
     }
     __device__ Pts load(size_t P) const {
@@ -2611,6 +2623,8 @@ struct TiledCorrFluxUpdate : TiledBase<T> {
             acc[1] += usq;
             const double nrho = -(rref + (double)r);
             acc[2] = nrho > acc[2] ? nrho : acc[2];
+            const double sg = courant_rate(fp, fm, r, rref, V);
+            acc[3] = sg > acc[3] ? sg : acc[3];
         }
     }
 };
@@ -2770,16 +2784,16 @@ void Ops<T>::cfl(const Launch& L, hipStream_t s, const Phys& ph, const DevState*
 }
 template <typename T>
 void Ops<T>::predict(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
-                     DevState* st, const double* part_cfl, double dt_fixed, double cfl,
-                     double growth, double dt_max, const T* rn, const T* un, const T* phi, T* rs,
-                     T* aP, T* divu, T* pn) {
+                     DevState* st, const double* part_cfl, unsigned nb_cfl, double dt_fixed,
+                     double cfl, double growth, double dt_max, const T* rn, const T* un,
+                     const T* phi, T* rs, T* aP, T* divu, T* pn) {
     if (TL.nblocks) {
         TiledPredict<T> k{};
         for (int d = 0; d < 3; ++d) k.sf[d] = un + d * ph.NT;
         k.face = phi;
         k.st0 = st;
         k.part_cfl = part_cfl;
-        k.nb_cfl = L.nblocks;
+        k.nb_cfl = nb_cfl;
         k.dt_fixed = dt_fixed;
         k.cfl = cfl;
         k.growth = growth;
@@ -2792,7 +2806,7 @@ void Ops<T>::predict(const Launch& L, const Launch& TL, hipStream_t s, const Phy
         tiled_launch<T>(TL, s, ph, st, k);
         return;
     }
-    LAUNCH(k_predict<T>, L, s, ph, st, part_cfl, L.nblocks, dt_fixed, cfl, growth, dt_max, rn, un,
+    LAUNCH(k_predict<T>, L, s, ph, st, part_cfl, nb_cfl, dt_fixed, cfl, growth, dt_max, rn, un,
            phi, rs, aP, divu, pn);
 }
 template <typename T>

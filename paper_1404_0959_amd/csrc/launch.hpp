@@ -51,11 +51,11 @@ constexpr int kCgCols = 7;
 
 // Partial-sum slots in the workspace (columns of num_blocks doubles each).
 enum PartSlot {
-    PS_CFL = 0,    // 1 column: Courant maxima
-    PS_U = 1,      // 3 columns: r.z, r.r, b.b (CG system set-up)
-    PS_CG = 4,     // 2 x kCgCols columns: CG iteration k in set k & 1
+    PS_U = 0,      // 3 columns: r.z, r.r, b.b (CG system set-up)
+    PS_CG = 3,     // 2 x kCgCols columns: CG iteration k in set k & 1
     PS_MASS = PS_CG + 2 * kCgCols,   // 3 columns: sum r, sum |u|^2, max(-rho)
-    PS_STAT = PS_MASS + 3,           // 4 columns: statistics
+    PS_CFL = PS_MASS + 3,            // 1 column: Courant maxima (k_cfl); must follow PS_MASS
+    PS_STAT = PS_CFL + 1,            // 4 columns: statistics
     PS_DUST = PS_STAT + 4,           // kMaxClasses columns: dust class masses
     PS_COLUMNS = PS_DUST + kMaxClasses
 };
@@ -92,12 +92,13 @@ struct Ops {
                          const T* r, const T* u, T* phi);
     static void cfl(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                     const T* r, const T* phi, double* part);
-    // TL: the tiled z-march when available (the Courant partials come from
-    // cfl over L)
+    // TL: the tiled z-march when available; nb_cfl: the number of Courant
+    // partials in part_cfl (from cfl, or from the previous step's last
+    // corrector pass)
     static void predict(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
-                        DevState* st, const double* part_cfl, double dt_fixed, double cfl,
-                        double growth, double dt_max, const T* rn, const T* un, const T* phi,
-                        T* rs, T* aP, T* divu, T* pn);
+                        DevState* st, const double* part_cfl, unsigned nb_cfl, double dt_fixed,
+                        double cfl, double growth, double dt_max, const T* rn, const T* un,
+                        const T* phi, T* rs, T* aP, T* divu, T* pn);
     // Field kernels taking TL run as k_tiled z-marches when TL.nblocks > 0;
     // those that write partials return how many (blocks of the launch used).
     static void mom_source(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
@@ -134,7 +135,10 @@ struct Ops {
                           const DevState* st, const T* p0, const T* x, const T* w,
                           const T* phiH, T* phik, T* pt, double* snap_x);
     // corr_flux and corr_update in one tiled pass (TL.nblocks > 0), p not
-    // stored; returns the number of mass partials written (last corrector)
+    // stored; the last corrector writes, from part_mass on, columns of nb
+    // partials each: the three of the mass budget, then the Courant maxima of
+    // the new state (4 nb <= 4 max_blocks: within PS_MASS and PS_CFL).
+    // Returns nb, the launch's block count.
     static unsigned corr_finish_fused(const Launch& TL, hipStream_t s, const Phys& ph,
                                       const DevState* st, bool last, const T* p0, const T* x,
                                       const T* w, const T* phiH, T* phik, double* snap_x,

@@ -200,6 +200,13 @@ struct pisoc_ctx {
     Launch TL;      // tiled z-marching launch of the field kernels (nblocks = 0: none)
     unsigned nb_start = 0;   // partials in PS_U of the current solve's start (its set-up kernel)
     unsigned nb_mass = 0;    // partials in PS_MASS (the last corrector update)
+    // Courant partials of the current state: nb_cfl of them at cfl_part,
+    // written by k_cfl (PS_CFL) or, when cfl_ready, by the final corrector
+    // pass of the last accepted eager step (the column after the mass
+    // partials); nb_cfl_next: that pass in the step being enqueued (0: none)
+    bool cfl_ready = false;
+    unsigned nb_cfl = 0, nb_cfl_next = 0;
+    const double* cfl_part = nullptr;
     Launch TS;      // tiled launch of the CG first half (nblocks = 0: none)
     DevState* st;
     DevState* hst = nullptr;  // pinned host copy (batch entries)
@@ -480,8 +487,9 @@ CgVecs<T> cg_vecs(const StepPtrs<T>& S) {
 
 // dt, density predictor, momentum source and predictor sweeps (u* ends in
 // the u slot ctx->ucur_slot).
+// cfl_ready: the Courant partials of the current state are already in PS_CFL.
 template <typename T>
-void enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S) {
+void enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
     using O = Ops<T>;
     const pisoc_params& p = ctx->prm;
     const Phys& ph = ctx->ph;
@@ -489,10 +497,14 @@ void enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S) {
     hipStream_t s = ctx->stream;
     DevState* st = ctx->st;
     clear_flags(s, st, ctx->batch);
-    timed(ctx, KC_CFL, 4, -1, [&] { O::cfl(L, s, ph, st, S.rn, S.phin, ctx->part(PS_CFL)); });
+    if (!cfl_ready) {
+        timed(ctx, KC_CFL, 4, -1, [&] { O::cfl(L, s, ph, st, S.rn, S.phin, ctx->part(PS_CFL)); });
+        ctx->nb_cfl = L.nblocks;
+        ctx->cfl_part = ctx->part(PS_CFL);
+    }
     timed(ctx, KC_PREDICT, 11, -1, [&] {
-        O::predict(L, ctx->TL, s, ph, st, ctx->part(PS_CFL), p.dt_fixed, p.cfl, p.dt_growth, p.dt_max, S.rn,
-                   S.un, S.phin, S.rk, S.aP, S.divu, S.pn);
+        O::predict(L, ctx->TL, s, ph, st, ctx->cfl_part, ctx->nb_cfl, p.dt_fixed, p.cfl,
+                   p.dt_growth, p.dt_max, S.rn, S.un, S.phin, S.rk, S.aP, S.divu, S.pn);
     });
     timed(ctx, KC_MOM_SOURCE, 8, -1,
           [&] { O::mom_source(L, ctx->TL, s, ph, st, S.rn, S.un, S.divu, S.src); });
@@ -546,10 +558,12 @@ void enqueue_corr_finish(pisoc_ctx* ctx, StepPtrs<T>& S, int corr) {
         // flux correction and update in one tiled pass (words: w, p0, p', phiH x3,
         // HbyA x3, rho^n, a_P read; phi x3, rho_k, u x3 written)
         timed(ctx, KC_CORR_UPDATE, 18, -1, [&] {
+            // the last pass also leaves the Courant partials of the new state
             ctx->nb_mass = O::corr_finish_fused(ctx->TL, s, ph, ctx->st, last, S.p0, S.x, S.w,
                                                 S.phiH, S.phik, cap ? S.snap + 3 * N : nullptr,
                                                 S.rn, S.hb, S.aP, S.rk, ucur, ctx->part(PS_MASS));
         });
+        if (last) ctx->nb_cfl_next = ctx->nb_mass;
         return;
     }
     timed(ctx, KC_CORR_FLUX, 10, -1, [&] {
@@ -721,7 +735,11 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
     const pisoc_params& p = ctx->prm;
     StepPtrs<T> S = step_ptrs<T>(ctx);
     hipStream_t s = ctx->stream;
-    enqueue_front<T>(ctx, S);
+    // an eager step reuses the Courant partials the previous accepted step left
+    const bool cfl_ready = eager && ctx->cfl_ready;
+    ctx->cfl_ready = false;
+    ctx->nb_cfl_next = 0;
+    enqueue_front<T>(ctx, S, cfl_ready);
     const bool audit = eager && audit_on(ctx);
     for (int corr = 0; corr < p.n_corr; ++corr) {
         const bool guess = p.guess == PISOC_GUESS_LEARNED && (!audit || ctx->audit.use[corr]);
@@ -845,6 +863,12 @@ pisoc_status eager_step(pisoc_ctx* ctx, pisoc_step_info* info) {
         }
     rotate(ctx);
     commit(ctx->stream, ctx->st, ctx->batch);
+    ctx->cfl_ready = ctx->nb_cfl_next > 0;
+    if (ctx->cfl_ready) {
+        // column 3 of the pass's block_partials, nb_cfl_next apart
+        ctx->nb_cfl = ctx->nb_cfl_next;
+        ctx->cfl_part = ctx->part(PS_MASS) + 3 * (size_t)ctx->nb_cfl;
+    }
     ctx->t += ctx->hst[0].dt;
     ctx->steps += 1;
     return worst;

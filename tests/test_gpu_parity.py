@@ -181,7 +181,9 @@ def test_tiled_kernels_match_gathered(P, monkeypatch, precision, n):
     agree and the fields agree to rounding (FP64: 1e-11 of the spread; FP32:
     the bound of the FP32 tests, 5e-5 of the spread plus 16 FP32 ulps of the
     magnitude -- a dust density of 1e-3 with a spread of 1e-5 after two steps
-    differs by a few ulps of its stored value)."""
+    differs by a few ulps of its stored value).  The tiled step 2 takes its
+    Courant maxima from step 1's last corrector pass, the gathered one from
+    k_cfl: the time steps agree exactly."""
     case = make_hit_case(n, 7, mach=0.5, stokes=(0.1, 0.4))
     kw = dict(p_tol=1e-9) if precision == "fp64" else dict(
         p_tol=1e-6, precision=P.FP32_REFINED, inner_tol=1e-6)
@@ -193,10 +195,11 @@ def test_tiled_kernels_match_gathered(P, monkeypatch, precision, n):
         st, info = s.step(2)
         assert st == 0
         runs.append((gpu_fields(P, s), [i["pcg_iters"] for i in info],
-                     [i["mass_gas"] for i in info]))
+                     [i["mass_gas"] for i in info], [i["dt"] for i in info]))
         monkeypatch.delenv("PISOC_UNTILED", raising=False)
-    (fa, ia, ma), (fb, ib, mb) = runs
+    (fa, ia, ma, da), (fb, ib, mb, db) = runs
     assert ia == ib
+    assert da == db
     mass_tol = 1e-12 if precision == "fp64" else 1e-10   # FP32: sums of FP32-stored densities
     for a, b in zip(ma, mb):
         assert abs(a - b) <= mass_tol * abs(a)
