@@ -831,15 +831,20 @@ __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
 // stencil, r_k = r_{k-1} - alpha_{k-1} q_{k-1}, z_k = r_k / diag (not stored)
 // and the direction p_k = z_k + beta_k p_{k-1}; iteration 0 takes p_0 = z_0.
 // Then q_k = M p_k with the face coefficients K = I4(w) formed on the fly; the
-// kernel stores r_k, p_k and q_k, applies x_k = x_{k-1} + alpha_{k-1} p_{k-1}
-// (p_{k-1} is read anyway; also on the stop path) and writes the partial sums
-// from which the next iteration takes its scalars (cg_head).  The iterates
+// kernel stores r_k, p_k and q_k and writes the partial sums from which the
+// next iteration takes its scalars (cg_head).  x is updated every other
+// iteration: an even k >= 2 applies x += alpha_{k-2} p_{k-2} + alpha_{k-1}
+// p_{k-1} (p_{k-1} is read anyway), an odd k leaves x alone; the stop
+// iteration adds what is still due (one term at an odd k, two at an even
+// k).  The rounding is that of adding the terms one iteration at a time.  The iterates
 // are those of textbook PCG; r_k.z_k and ||r_k||^2 are expanded from sums of
 // iteration k-1 instead of being summed over r_k, so one global reduction per
-// iteration suffices.  r, p and q alternate between two buffers (iteration k
-// reads the k-1 values on the stencil while writing its own).  With xzero
-// (the solve started from x = 0, not written) the kernel writes x at k = 1
-// and, on a stop at k = 0, zeroes it.
+// iteration suffices.  r and q alternate between two buffers (iteration k
+// reads the k-1 values on the stencil while writing its own), p rotates
+// through three (an even k also reads p_{k-2}).  With xzero (the solve
+// started from x = 0, not written) the first write of x sets it: at k = 2,
+// or on a stop at k = 1 (x = alpha_0 p_0) or k = 0 (x = 0).  XM: 0 for k = 0,
+// 1 for odd k, 2 for even k >= 2.
 
 // Partial-sum columns of iteration k (FP64 sums of products of the stored
 // values): p.q, q.z, q.(q/diag), q.r, q.q, r.z, r.r over r_k, z_k = r_k / diag
@@ -910,6 +915,7 @@ __device__ inline CgHead cg_head(const Phys& ph, PcgState& g, bool recorder, int
     if (recorder) {
         g.rr = h.rr;
         g.iters = k;
+        if (k >= 1) g.alphah[k & 1] = h.alpha;
         if (newb) g.bb = bb;
         if (h.stop) {
             g.it_stop = k;
@@ -919,13 +925,34 @@ __device__ inline CgHead cg_head(const Phys& ph, PcgState& g, bool recorder, int
     return h;
 }
 
-// Gathered form (any n).  UPD: k >= 1.
-template <typename T, bool UPD>
+// The x update of iteration k (see above): alpha = alpha_{k-1}, alpha2 =
+// alpha_{k-2}; set: x not written yet (xzero and k <= 2).  V: T or a vector of T.
+template <typename T>
+struct CgX {
+    T alpha, alpha2;
+    bool set;
+    template <typename V>
+    __device__ V one(V xo, V p1) const { return set ? alpha * p1 : xo + alpha * p1; }
+    template <typename V>
+    __device__ V two(V xo, V p2, V p1) const {
+        const V t = set ? alpha2 * p2 : xo + alpha2 * p2;
+        return t + alpha * p1;
+    }
+};
+template <typename T, int XM>
+__device__ inline CgX<T> cg_x(const PcgState& g, int k, double alpha, int xzero) {
+    return {(T)alpha, XM == 2 ? (T)g.alphah[(k - 1) & 1] : T(0), xzero != 0 && k <= 2};
+}
+
+// Gathered form (any n).
+template <typename T, int XM>
 __global__ void __launch_bounds__(kBlock) k_pcg_spmv(
     Phys ph, DevState* st, int k, const T* __restrict__ rin, T* __restrict__ rout,
     const T* __restrict__ diag, const T* __restrict__ w, const T* __restrict__ pold,
-    T* __restrict__ pnew, const T* __restrict__ qold, T* __restrict__ q, T* __restrict__ x,
-    const double* part_in, unsigned nb_in, double* part_out, int fresh, int maxit, int xzero) {
+    const T* __restrict__ pold2, T* __restrict__ pnew, const T* __restrict__ qold,
+    T* __restrict__ q, T* __restrict__ x, const double* part_in, unsigned nb_in, double* part_out,
+    int fresh, int maxit, int xzero) {
+    constexpr bool UPD = XM > 0, XE = XM == 2;
     MEMBER(ph)
     // it_stop == k is this launch's own decision, written by the member's
     // first block: the other blocks must still take the stop path below
@@ -933,12 +960,11 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(
     const CgHead h = cg_head(ph, (st + mem_)->pcg, MEMBER_FIRST(), mem_, k, part_in, nb_in, fresh,
                              maxit);
     const T alpha = (T)h.alpha, beta = (T)h.beta;
-    const bool xset = UPD && k == 1 && xzero;
-    auto xnew = [&](T xo, T po) { return xset ? alpha * po : xo + alpha * po; };
+    const CgX<T> xu = cg_x<T, XM>((st + mem_)->pcg, k, h.alpha, xzero);
     if (h.stop) {
         if (UPD || xzero) {
             FOR_CELLS(ph)
-            x[P] = UPD ? xnew(x[P], pold[P]) : T(0);
+            x[P] = XE ? xu.two(x[P], pold2[P], pold[P]) : UPD ? xu.one(x[P], pold[P]) : T(0);
             END_CELLS
         }
         return;
@@ -963,10 +989,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(
         sumK += kp + km;
     }
     const T qP = (dP - sumK * inv_h2) * pP + lap * inv_h2;
-    if (UPD) {
-        rout[P] = rP;
-        x[P] = xnew(x[P], pold[P]);
-    }
+    if (UPD) rout[P] = rP;
+    if (XE) x[P] = xu.two(x[P], pold2[P], pold[P]);
     pnew[P] = pP;
     q[P] = qP;
     cg_accumulate(v, pP, qP, rP, zP, iP);
@@ -979,12 +1003,14 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(
 // from HBM: the x-y neighbours of the current plane come from LDS tiles (halo
 // 2 for w; halo 1 for the direction p, formed from r, q, p_old and diag at
 // the halo cells), the z neighbours from per-thread register queues.
-template <typename T, int RPT, bool UPD>
+template <typename T, int RPT, int XM>
 __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     Phys ph, DevState* st, int k, const T* __restrict__ rin, T* __restrict__ rout,
     const T* __restrict__ diag, const T* __restrict__ w, const T* __restrict__ pold,
-    T* __restrict__ pnew, const T* __restrict__ qold, T* __restrict__ q, T* __restrict__ x,
-    const double* part_in, unsigned nb_in, double* part_out, int fresh, int maxit, int xzero) {
+    const T* __restrict__ pold2, T* __restrict__ pnew, const T* __restrict__ qold,
+    T* __restrict__ q, T* __restrict__ x, const double* part_in, unsigned nb_in, double* part_out,
+    int fresh, int maxit, int xzero) {
+    constexpr bool UPD = XM > 0, XE = XM == 2;
     MEMBER(ph)
     if (k > (st + mem_)->pcg.it_stop) return;   // see k_pcg_spmv
     const CgHead h = cg_head(ph, (st + mem_)->pcg, MEMBER_FIRST(), mem_, k, part_in, nb_in, fresh,
@@ -998,8 +1024,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     const int k0 = bz_ * cz;
     const int k1 = k0 + cz < n ? k0 + cz : n;
     const size_t nn = (size_t)n * n;
-    const bool xset = UPD && k == 1 && xzero;
-    auto xnew = [&](T xo, T po) { return xset ? alpha * po : xo + alpha * po; };
+    const CgX<T> xu = cg_x<T, XM>((st + mem_)->pcg, k, h.alpha, xzero);
     if (h.stop) {
         if (UPD || xzero) {
 #pragma unroll
@@ -1007,7 +1032,9 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
                 const size_t c0 = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty + e * kTY);
                 for (int kk = k0; kk < k1; ++kk) {
                     const size_t Q = c0 + nn * (size_t)kk;
-                    x[Q] = UPD ? xnew(x[Q], pold[Q]) : T(0);
+                    x[Q] = XE    ? xu.two(x[Q], pold2[Q], pold[Q])
+                           : UPD ? xu.one(x[Q], pold[Q])
+                                 : T(0);
                 }
             }
         }
@@ -1023,7 +1050,9 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     T wq0[RPT], wq1[RPT], wq2[RPT], wq3[RPT], wq4[RPT], pm[RPT], pc[RPT], rc[RPT], zc[RPT], dc[RPT];
     T ic[RPT];   // jinv(diag) of the current plane
     T rn1[RPT], qn1[RPT], dn1[RPT], on1[RPT];
-    T oc[RPT], xc[RPT], xn1[RPT];   // UPD: p_old and x of the current plane, x one plane ahead
+    // p_old of the current plane; XE: x and p_{k-2} of the current plane and
+    // one plane ahead
+    T oc[RPT], xc[RPT], xn1[RPT], o2c[RPT], o2n1[RPT];
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
         col[e] = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty + e * kTY);
@@ -1039,7 +1068,10 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
         zc[e] = rc[e] * ic[e];
         oc[e] = UPD ? pold[Q0] : T(0);
         pc[e] = dirf(zc[e], oc[e]);
-        if (UPD) xc[e] = x[Q0];
+        if (XE) {
+            xc[e] = stream_ld(x + Q0);
+            o2c[e] = stream_ld(pold2 + Q0);
+        }
     }
     // this thread's halo cell, if any (same x-y position on every plane):
     // w rows j0-2, j0-1, j0+TY, j0+TY+1; w columns i0-2, i0-1, i0+64, i0+65;
@@ -1127,7 +1159,11 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
                 if (UPD) {
                     qn1[e] = qold[Qf];
                     on1[e] = pold[Qf];
-                    xn1[e] = stream_ld(x + col[e] + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk));
+                }
+                if (XE) {
+                    const size_t Qx = col[e] + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk);
+                    xn1[e] = stream_ld(x + Qx);
+                    o2n1[e] = stream_ld(pold2 + Qx);
                 }
             }
             ha = hsrc[Hf];
@@ -1166,10 +1202,8 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
             const T qv = (dc[e] - sumK * inv_h2) * c0 + lap * inv_h2;
             stream_st(q + (col[e] + pl), qv);
             stream_st(pnew + (col[e] + pl), c0);
-            if (UPD) {
-                stream_st(rout + (col[e] + pl), rc[e]);
-                stream_st(x + (col[e] + pl), xnew(xc[e], oc[e]));
-            }
+            if (UPD) stream_st(rout + (col[e] + pl), rc[e]);
+            if (XE) stream_st(x + (col[e] + pl), xu.two(xc[e], o2c[e], oc[e]));
             cg_accumulate(acc, c0, qv, rc[e], zc[e], ic[e]);
         }
         lds_barrier();
@@ -1185,9 +1219,10 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
             zc[e] = zp[e];
             ic[e] = ip[e];
             dc[e] = dn[e];
-            if (UPD) {
-                oc[e] = on[e];
+            if (UPD) oc[e] = on[e];
+            if (XE) {
                 xc[e] = xn1[e];
+                o2c[e] = o2n1[e];
             }
         }
     }
@@ -1203,12 +1238,14 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
 // loaded by wavefronts 0-5; z neighbours from per-lane register queues, the
 // lower z face coefficient carried over from the plane below.  Prefetches
 // past the chunk's last needed plane are clamped to planes already read.
-template <typename T, int V, bool UPD>
+template <typename T, int V, int XM>
 __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     Phys ph, DevState* st, int k, const T* __restrict__ rin, T* __restrict__ rout,
     const T* __restrict__ diag, const T* __restrict__ w, const T* __restrict__ pold,
-    T* __restrict__ pnew, const T* __restrict__ qold, T* __restrict__ q, T* __restrict__ x,
-    const double* part_in, unsigned nb_in, double* part_out, int fresh, int maxit, int xzero) {
+    const T* __restrict__ pold2, T* __restrict__ pnew, const T* __restrict__ qold,
+    T* __restrict__ q, T* __restrict__ x, const double* part_in, unsigned nb_in, double* part_out,
+    int fresh, int maxit, int xzero) {
+    constexpr bool UPD = XM > 0, XE = XM == 2;
     using VT = T __attribute__((ext_vector_type(V)));
     static_assert(kRowWaves >= 6, "wavefronts 0-5 load the y halo rows");
     MEMBER(ph)
@@ -1231,17 +1268,16 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     // outputs and x stream past the caches (stream_st), keeping L2 for the
     // halo rows and planes still to be read
     auto st_v = [](T* f, size_t o, VT v) { stream_st(reinterpret_cast<VT*>(f + o), v); };
-    auto ld_x = [](const T* f, size_t o) {
-        return __builtin_nontemporal_load(reinterpret_cast<const VT*>(f + o));
-    };
+    auto ld_x = [](const T* f, size_t o) { return stream_ld(reinterpret_cast<const VT*>(f + o)); };
     const size_t col = base_ + (size_t)n * (j0 + wv) + (size_t)V * lane;
-    const bool xset = UPD && k == 1 && xzero;
-    auto xnew = [&](VT xo, VT po) { return xset ? alpha * po : xo + alpha * po; };
+    const CgX<T> xu = cg_x<T, XM>((st + mem_)->pcg, k, h.alpha, xzero);
     if (h.stop) {
         if (UPD || xzero) {
             for (int kk = k0; kk < k1; ++kk) {
                 const size_t Q = col + nn * (size_t)kk;
-                st_v(x, Q, UPD ? xnew(ld(x, Q), ld(pold, Q)) : VT(T(0)));
+                st_v(x, Q, XE    ? xu.two(ld(x, Q), ld(pold2, Q), ld(pold, Q))
+                           : UPD ? xu.one(ld(x, Q), ld(pold, Q))
+                                 : VT(T(0)));
             }
         }
         return;
@@ -1279,7 +1315,9 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     VT rc = resf(ld(rin, Q0), ldu(qold, Q0));
     VT ic = jv(dc), zc = rc * ic;
     VT pc = dirf(zc, oc);
-    VT xc = UPD ? ld(x, Q0) : VT(T(0)), xn1 = xc;
+    // XE: x and p_{k-2} of the current plane and one plane ahead
+    VT xc = XE ? ld_x(x, Q0) : VT(T(0)), xn1 = xc;
+    VT o2c = XE ? ld_x(pold2, Q0) : VT(T(0)), o2n1 = o2c;
     VT rnx = ld(rin, Q1), qnx = ldu(qold, Q1), dnx = ld(diag, Q1), onx = ldu(pold, Q1);
     VT h1 = ld(hsrc, hcol + plane(k0)), h2 = ld(hdsrc, hcol + plane(k0));
     VT h3 = ldu(hosrc, hcol + plane(k0)), h4 = ldu(hqsrc, hcol + plane(k0));
@@ -1310,7 +1348,11 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
             h2 = ld(hdsrc, Qh);
             h3 = ldu(hosrc, Qh);
             h4 = ldu(hqsrc, Qh);
-            if (UPD) xn1 = ld_x(x, col + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk));
+            if (XE) {
+                const size_t Qx = col + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk);
+                xn1 = ld_x(x, Qx);
+                o2n1 = ld_x(pold2, Qx);
+            }
         }
         wl[wv + 2][lane] = w0;
         pl[wv + 1][lane] = pc;
@@ -1357,12 +1399,13 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
         const size_t pl0 = nn * (size_t)kk;
         st_v(q, col + pl0, qo);
         st_v(pnew, col + pl0, pc);
-        if (UPD) {
-            st_v(rout, col + pl0, rc);
-            st_v(x, col + pl0, xnew(xc, oc));
+        if (UPD) st_v(rout, col + pl0, rc);
+        if (XE) {
+            st_v(x, col + pl0, xu.two(xc, o2c, oc));
             xc = xn1;
-            oc = on;
+            o2c = o2n1;
         }
+        if (UPD) oc = on;
         wm1 = w0;
         w0 = wp1;
         wp1 = wp2;
@@ -2892,17 +2935,17 @@ unsigned Ops<T>::refine(const Launch& L, const Launch& TL, hipStream_t s, const 
         LAUNCH((k_refine<T, false>), L, s, ph, st, x64, d, x64n, b64, w, diag, r32, part_u);
     return L.nblocks;
 }
-template <typename T, bool UPD>
+template <typename T, int XM>
 static void spmv_launch(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                         DevState* st, int k, const CgArgs<T>& a) {
-#define SPMV_ARGS st, k, a.rin, a.rout, a.diag, a.w, a.pold, a.pnew, a.qold, a.q, a.x, a.part_in, \
-                  a.nb_in, a.part_out, a.fresh, a.maxit, a.xzero
+#define SPMV_ARGS st, k, a.rin, a.rout, a.diag, a.w, a.pold, a.pold2, a.pnew, a.qold, a.q, a.x, \
+                  a.part_in, a.nb_in, a.part_out, a.fresh, a.maxit, a.xzero
     if constexpr (sizeof(T) == 4) {
         if (TL.nblocks && TL.v == kRowCells) {
             Phys pt = ph;
             pt.cz = TL.cz;
             pt.nz = TL.nz;
-            LAUNCH((k_pcg_spmv_rows<T, kRowCells, UPD>), TL, s, pt, SPMV_ARGS);
+            LAUNCH((k_pcg_spmv_rows<T, kRowCells, XM>), TL, s, pt, SPMV_ARGS);
             return;
         }
     }
@@ -2910,9 +2953,9 @@ static void spmv_launch(const Launch& L, const Launch& TL, hipStream_t s, const 
         Phys pt = ph;
         pt.cz = TL.cz;
         pt.nz = TL.nz;
-        LAUNCH((k_pcg_spmv_tiled<T, kSpmvRows, UPD>), TL, s, pt, SPMV_ARGS);
+        LAUNCH((k_pcg_spmv_tiled<T, kSpmvRows, XM>), TL, s, pt, SPMV_ARGS);
     } else {
-        LAUNCH((k_pcg_spmv<T, UPD>), L, s, ph, SPMV_ARGS);
+        LAUNCH((k_pcg_spmv<T, XM>), L, s, ph, SPMV_ARGS);
     }
 #undef SPMV_ARGS
 }
@@ -2920,9 +2963,11 @@ template <typename T>
 void Ops<T>::pcg_iter(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                       DevState* st, int k, const CgArgs<T>& a) {
     if (k == 0)
-        spmv_launch<T, false>(L, TL, s, ph, st, k, a);
+        spmv_launch<T, 0>(L, TL, s, ph, st, k, a);
+    else if (k & 1)
+        spmv_launch<T, 1>(L, TL, s, ph, st, k, a);
     else
-        spmv_launch<T, true>(L, TL, s, ph, st, k, a);
+        spmv_launch<T, 2>(L, TL, s, ph, st, k, a);
 }
 template <typename T>
 void Ops<T>::helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt, const T* w,

@@ -61,8 +61,9 @@ enum PartSlot {
 };
 
 // Operands of CG iteration k.  Reads r_{k-1}, p_{k-1}, q_{k-1} (rin, pold,
-// qold; only rin = r_0 at k = 0), diag and w; writes r_k (k >= 1), p_k, q_k
-// and updates x.  part_in: the partials of iteration k-1 (kCgCols columns),
+// qold; only rin = r_0 at k = 0), diag and w, and at even k >= 2 p_{k-2}
+// (pold2) and x; writes r_k (k >= 1), p_k, q_k and, at even k and at the
+// stop, x.  part_in: the partials of iteration k-1 (kCgCols columns),
 // at k = 0 those of the set-up kernel (r.z, r.r, b.b), written by nb_in
 // blocks; part_out: this iteration's.  fresh: the set-up's b.b is the
 // reference ||b||^2 of the solve; xzero: the solve started from x = 0 without
@@ -71,7 +72,7 @@ template <typename T>
 struct CgArgs {
     const T* rin;
     T* rout;
-    const T *diag, *w, *pold;
+    const T *diag, *w, *pold, *pold2;
     T* pnew;
     const T* qold;
     T *q, *x;

@@ -61,7 +61,7 @@ std::vector<std::pair<int, int>> shape_candidates(int n) {
 // Byte offsets of every buffer inside the workspace (all members of a batch).
 struct Layout {
     size_t state, partials;
-    size_t rn, rk, aP, divu, pn, w, p0, r, r2, x, diag, pp0, pp1, q, q2, Y0, Y1;
+    size_t rn, rk, aP, divu, pn, w, p0, r, r2, x, diag, pp0, pp1, pp2, q, q2, Y0, Y1;
     size_t u3[3], phin, phik, src, hbya, phiH, acc, G;
     size_t rhop, rhop1;
     size_t snap;   // 4 FP64 fields when capturing
@@ -162,7 +162,7 @@ Layout make_layout(const pisoc_params* p, int batch) {
     L.state = take(sizeof(DevState) * (size_t)batch);
     L.partials = take(sizeof(double) * PS_COLUMNS * (size_t)L.max_blocks);
     size_t* one[] = {&L.rn, &L.rk, &L.aP, &L.divu, &L.pn, &L.w, &L.p0, &L.r, &L.r2, &L.x,
-                     &L.diag, &L.pp0, &L.pp1, &L.q, &L.q2, &L.Y0, &L.Y1};
+                     &L.diag, &L.pp0, &L.pp1, &L.pp2, &L.q, &L.q2, &L.Y0, &L.Y1};
     for (size_t* o : one) *o = take(es * N);
     size_t* three[] = {&L.u3[0], &L.u3[1], &L.u3[2], &L.phin, &L.phik, &L.src, &L.hbya,
                        &L.phiH, &L.acc, &L.G};
@@ -313,11 +313,11 @@ void set_shape(pisoc_ctx* ctx, const Launch& L) {
     ctx->ph.nz = L.nz;
 }
 
-// The vectors of one CG solve: r_k, p_k and q_k in r[k & 1], p[k & 1],
+// The vectors of one CG solve: r_k, p_k and q_k in r[k & 1], p[k % 3],
 // q[k & 1] (the set-up kernel leaves r_0 in r[0]).
 template <typename T>
 struct CgVecs {
-    T *r[2], *p[2], *q[2];
+    T *r[2], *p[3], *q[2];
     T *x, *diag, *w;
 };
 
@@ -337,16 +337,17 @@ pisoc_status run_pcg(pisoc_ctx* ctx, const CgVecs<T>& v, bool fresh, int iters, 
     const int maxit = ctx->prm.p_maxit;
     const unsigned nb_cg = ctx->TS.nblocks ? ctx->TS.nblocks : ctx->L.nblocks;
     auto iter = [&](int k) {
-        // words: r, diag, w read, p, q written; from k = 1 also q, p_old read, r written and
-        // x updated
-        timed(ctx, KC_PCG_SPMV, k == 0 ? 5.0 : 10.0, k, [&] {
+        // words: r, diag, w read, p, q written; from k = 1 also q, p_old read and r written;
+        // at even k >= 2 also p_{k-2} read and x updated
+        timed(ctx, KC_PCG_SPMV, k == 0 ? 5.0 : (k & 1) ? 8.0 : 11.0, k, [&] {
             CgArgs<T> a;
             a.rin = v.r[k == 0 ? 0 : (k + 1) & 1];
             a.rout = v.r[k & 1];
             a.diag = v.diag;
             a.w = v.w;
-            a.pold = v.p[(k + 1) & 1];
-            a.pnew = v.p[k & 1];
+            a.pold = v.p[(k + 2) % 3];
+            a.pold2 = v.p[(k + 1) % 3];
+            a.pnew = v.p[k % 3];
             a.qold = v.q[(k + 1) & 1];
             a.q = v.q[k & 1];
             a.x = v.x;
@@ -423,7 +424,7 @@ void learned_guess(pisoc_ctx* ctx, T* r, T* x, T* dg, T* w, T* p0, T* gbuf, T* m
 template <typename T>
 struct StepPtrs {
     T *rn, *rk, *un, *ua, *ub, *phin, *phik;
-    T *aP, *divu, *pn, *src, *hb, *w, *p0, *phiH, *r, *r2, *x, *dg, *pp0, *pp1, *q, *q2;
+    T *aP, *divu, *pn, *src, *hb, *w, *p0, *phiH, *r, *r2, *x, *dg, *pp0, *pp1, *pp2, *q, *q2;
     T *acc, *G, *Ya, *Yb, *rj, *rj1;
     double *snap, *b64, *x64a, *x64b;
 };
@@ -454,6 +455,7 @@ StepPtrs<T> step_ptrs(const pisoc_ctx* ctx) {
     P.dg = F(Y.diag);
     P.pp0 = F(Y.pp0);
     P.pp1 = F(Y.pp1);
+    P.pp2 = F(Y.pp2);
     P.q = F(Y.q);
     P.q2 = F(Y.q2);
     P.acc = F(Y.acc);
@@ -477,6 +479,7 @@ CgVecs<T> cg_vecs(const StepPtrs<T>& S) {
     v.r[1] = S.r2;
     v.p[0] = S.pp0;
     v.p[1] = S.pp1;
+    v.p[2] = S.pp2;
     v.q[0] = S.q;
     v.q[1] = S.q2;
     v.x = S.x;
@@ -1809,6 +1812,7 @@ static Layout helm_layout(int32_t n) {
     L.diag = take(8 * N);
     L.pp0 = take(8 * N);
     L.pp1 = take(8 * N);
+    L.pp2 = take(8 * N);
     L.q = take(8 * N);
     L.q2 = take(8 * N);
     L.total = off;
@@ -1889,6 +1893,7 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
         v.r[1] = ctx.f<double>(lay.r2);
         v.p[0] = ctx.f<double>(lay.pp0);
         v.p[1] = ctx.f<double>(lay.pp1);
+        v.p[2] = ctx.f<double>(lay.pp2);
         v.q[0] = ctx.f<double>(lay.q);
         v.q[1] = ctx.f<double>(lay.q2);
         v.x = d_x;
