@@ -329,12 +329,13 @@ struct CgVecs {
 // iterations in batches, the first batch of `iters` after iteration 0, the
 // host waiting after each until every member has stopped; otherwise exactly
 // `iters` after iteration 0 (capture).  Returns the largest iteration count
-// (eager).
+// (eager).  cap > 0: the solve stops at iteration cap at the latest (taking x
+// up to date), as at p_maxit.
 template <typename T>
 pisoc_status run_pcg(pisoc_ctx* ctx, const CgVecs<T>& v, bool fresh, int iters, bool eager,
-                     int* iters_max, bool xzero, unsigned nb_first) {
+                     int* iters_max, bool xzero, unsigned nb_first, int cap = 0) {
     using O = Ops<T>;
-    const int maxit = ctx->prm.p_maxit;
+    const int maxit = cap > 0 ? std::min(cap, ctx->prm.p_maxit) : ctx->prm.p_maxit;
     const unsigned nb_cg = ctx->TS.nblocks ? ctx->TS.nblocks : ctx->L.nblocks;
     auto iter = [&](int k) {
         // words: r, diag, w read, p, q written; from k = 1 also q, p_old read and r written;
@@ -623,6 +624,18 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
                 nb_dust, ctx->lay.max_blocks);
 }
 
+// Iterations past a solve's predicted count that an eager FP32 first round
+// runs before it is stopped.
+constexpr int kSpecMargin = 2;
+
+// Latest stop iteration of corrector corr's first round over the members
+// (launches from it on did no CG work), from the state the host last read.
+int first_stop(const pisoc_ctx* ctx, int corr) {
+    int k = 0;
+    for (int m = 0; m < ctx->batch; ++m) k = std::max(k, ctx->hst[m].it_first[corr]);
+    return k;
+}
+
 // FP32 storage: mixed-precision iterative refinement of M p' = b for every
 // member.  guess: the first inner solve starts from the learned guess (x and
 // x64 set), else from zero.  The first inner FP32 solve runs to tau0 = max(p_tol/2, inner_tol)
@@ -644,12 +657,18 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
     *err = PISOC_OK;
     set_tol(s, ctx->st, B, tau0 * tau0);
     int most = 0;
-    const int pairs0 = eager ? (ctx->pred_first[corr] > 0 ? ctx->pred_first[corr] : 8) : ctx->caps[corr];
-    if ((*err = run_pcg<float>(ctx, cg_vecs(S), true, pairs0, eager,
-                               &most, !guess, ctx->nb_start)) != PISOC_OK)
+    // An eager first round does not wait for the host: it runs the
+    // iterations of the last step's first round plus kSpecMargin, the last
+    // of them stopping the solve; a round stopped there unconverged is taken
+    // up by the refinement.  The count is updated after the step.
+    const int cap0 = eager ? std::min((ctx->pred_first[corr] > 0 ? ctx->pred_first[corr] : 8) +
+                                          kSpecMargin, p.p_maxit)
+                           : ctx->caps[corr];
+    if ((*err = run_pcg<float>(ctx, cg_vecs(S), true, cap0, false, nullptr, !guess, ctx->nb_start,
+                               eager ? cap0 : 0)) != PISOC_OK)
         return;
-    if (eager) ctx->pred_first[corr] = most;
     record_solve(s, ctx->st, B, corr, /*round=*/1, /*add=*/1, /*fin=*/0);
+    bool waited = false;   // the host has seen the state since the first round
     const int max_rounds = eager ? p.max_refine : ctx->rounds;
     int round = 0;
     unsigned nb_ref = ctx->L.nblocks;   // partials of the last refinement
@@ -666,7 +685,8 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
         if (round >= max_rounds) break;
         if (eager) {
             if ((*err = sync_state(ctx)) != PISOC_OK) return;
-            if (ctx->prof.on) ctx->prof.resolve(kIterInf);
+            if (ctx->prof.on) ctx->prof.resolve(waited ? kIterInf : first_stop(ctx, corr));
+            waited = true;
             bool done = true;
             for (int m = 0; m < B; ++m) {
                 const DevState& h = ctx->hst[m];
@@ -682,6 +702,11 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
             return;
         if (eager) ctx->pred_later = most;
         record_solve(s, ctx->st, B, corr, round + 1, /*add=*/1, /*fin=*/0);
+    }
+    if (eager && ctx->prof.on && !waited) {
+        // attribute the first round's launches before later solves add more
+        if ((*err = sync_state(ctx)) != PISOC_OK) return;
+        ctx->prof.resolve(first_stop(ctx, corr));
     }
     record_solve(s, ctx->st, B, corr, round, /*add=*/0, /*fin=*/2);
     // the corrector uses the FP32 copy of the FP64 solution
@@ -833,6 +858,11 @@ pisoc_status eager_step(pisoc_ctx* ctx, pisoc_step_info* info) {
     if (st != PISOC_OK) return st;
     if ((st = sync_state(ctx)) != PISOC_OK) return st;
     if (ctx->prof.on) ctx->prof.resolve(kIterInf);
+    // first-round iteration counts: the next step's predictions
+    for (int c = 0; c < ctx->prm.n_corr; ++c) {
+        const int it = first_stop(ctx, c);
+        if (it > 0) ctx->pred_first[c] = it;
+    }
     int skipped = 0;
     if (audit_on(ctx)) {
         audit_update(ctx);
