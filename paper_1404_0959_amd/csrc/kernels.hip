@@ -774,7 +774,8 @@ __global__ void __launch_bounds__(kTX * kTY) k_corr_rhs_tiled(
 // set up the next inner solve's right-hand side float(r64) with partial sums
 // r.(r/diag), ||r64||^2, ||r64||^2.  FROM_ZERO: x64 is zero (the first round
 // of a solve started from zero) and is not read.  The next inner solve
-// starts from d = 0 without d being written.
+// starts from d = 0 without d being written.  x64_new is also written
+// rounded to T (xf): after the last round that is the corrector's solution.
 template <typename T>
 __device__ inline void refine_cell(const T (&wv)[13], const double (&xv)[7], const T (&dv)[7],
                                    double bP, T dgP, double inv_h2, double& xP, double& r) {
@@ -794,6 +795,7 @@ template <typename T, bool FROM_ZERO>
 __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
                                                    const double* __restrict__ x64,
                                                    const T* __restrict__ d, double* __restrict__ x64n,
+                                                   T* __restrict__ xf,
                                                    const double* __restrict__ b64,
                                                    const T* __restrict__ w, const T* __restrict__ diag,
                                                    T* __restrict__ r32, double* part_u) {
@@ -812,6 +814,7 @@ __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
     double xP, r;
     refine_cell(wv, xv, dv, bP, dgP, inv_h2, xP, r);
     x64n[P] = xP;
+    xf[P] = (T)xP;
     const T rT = (T)r;
     r32[P] = rT;
     v[0] += (double)rT * ((double)rT / (double)dgP);
@@ -2458,7 +2461,7 @@ struct TiledRefineFromZero : TiledBase<T> {
     const double* b64;
     const T* diag;
     double* x64n;
-    T* r32;
+    T *xf, *r32;
     double inv_h2;
     struct Pts { double b; T dg; };
     __device__ void member(const Phys& ph, const DevState*) { inv_h2 = ph.inv_h2; }
@@ -2472,6 +2475,7 @@ struct TiledRefineFromZero : TiledBase<T> {
         double xP, r;
         refine_cell(v[0], xv, dv, p.b, p.dg, inv_h2, xP, r);
         stream_st(x64n + P, xP);
+        stream_st(xf + P, (T)xP);
         const T rT = (T)r;
         stream_st(r32 + P, rT);
         acc[0] += (double)rT * ((double)rT / (double)p.dg);
@@ -2915,7 +2919,7 @@ unsigned Ops<T>::corr_rhs(const Launch& L, const Launch& TL, hipStream_t s, cons
 }
 template <typename T>
 unsigned Ops<T>::refine(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
-                        DevState* st, const double* x64, const T* d, double* x64n,
+                        DevState* st, const double* x64, const T* d, double* x64n, T* xf,
                         const double* b64, const T* w, const T* diag, T* r32, double* part_u,
                         bool from_zero) {
     if (from_zero && TL.nblocks) {
@@ -2926,13 +2930,14 @@ unsigned Ops<T>::refine(const Launch& L, const Launch& TL, hipStream_t s, const 
         k.b64 = b64;
         k.diag = diag;
         k.x64n = x64n;
+        k.xf = xf;
         k.r32 = r32;
         return tiled_launch<T>(TL, s, ph, st, k);
     }
     if (from_zero)
-        LAUNCH((k_refine<T, true>), L, s, ph, st, x64, d, x64n, b64, w, diag, r32, part_u);
+        LAUNCH((k_refine<T, true>), L, s, ph, st, x64, d, x64n, xf, b64, w, diag, r32, part_u);
     else
-        LAUNCH((k_refine<T, false>), L, s, ph, st, x64, d, x64n, b64, w, diag, r32, part_u);
+        LAUNCH((k_refine<T, false>), L, s, ph, st, x64, d, x64n, xf, b64, w, diag, r32, part_u);
     return L.nblocks;
 }
 template <typename T, int XM>

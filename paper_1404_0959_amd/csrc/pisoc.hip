@@ -65,7 +65,7 @@ struct Layout {
     size_t u3[3], phin, phik, src, hbya, phiH, acc, G;
     size_t rhop, rhop1;
     size_t snap;   // 4 FP64 fields when capturing
-    size_t b64, x64a, x64b;  // FP64 refinement fields (FP32 storage only)
+    size_t b64, x64a, x64b, xf;  // FP64 refinement fields, FP32 solution copy (FP32 storage only)
     size_t wpk, nx4, na, nb, ny, bsave;  // learned guess: packed weights, activations
     size_t total;
     unsigned max_blocks;     // column length of the partials (all members)
@@ -182,6 +182,7 @@ Layout make_layout(const pisoc_params* p, int batch) {
         L.b64 = take(sizeof(double) * N);
         L.x64a = take(sizeof(double) * N);
         L.x64b = take(sizeof(double) * N);
+        L.xf = take(sizeof(float) * N);
     }
     L.total = off;
     return L;
@@ -428,6 +429,7 @@ struct StepPtrs {
     T *aP, *divu, *pn, *src, *hb, *w, *p0, *phiH, *r, *r2, *x, *dg, *pp0, *pp1, *pp2, *q, *q2;
     T *acc, *G, *Ya, *Yb, *rj, *rj1;
     double *snap, *b64, *x64a, *x64b;
+    T* xf;   // FP32: the refinement's rounded solution (exchanged with x after a solve)
 };
 
 template <typename T>
@@ -470,6 +472,7 @@ StepPtrs<T> step_ptrs(const pisoc_ctx* ctx) {
     P.b64 = f32 ? ctx->f<double>(Y.b64) : nullptr;
     P.x64a = f32 ? ctx->f<double>(Y.x64a) : nullptr;
     P.x64b = f32 ? ctx->f<double>(Y.x64b) : nullptr;
+    P.xf = f32 ? F(Y.xf) : nullptr;
     return P;
 }
 
@@ -674,9 +677,9 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
     unsigned nb_ref = ctx->L.nblocks;   // partials of the last refinement
     for (;;) {
         const bool from_zero = round == 0 && !guess;
-        timed(ctx, KC_REFINE, from_zero ? 8 : 10, -1, [&] {
-            nb_ref = Ops<float>::refine(ctx->L, ctx->TL, s, ctx->ph, ctx->st, xa, S.x, xb, S.b64,
-                                        S.w, S.dg, S.r, ctx->part(PS_U), from_zero);
+        timed(ctx, KC_REFINE, from_zero ? 9 : 11, -1, [&] {
+            nb_ref = Ops<float>::refine(ctx->L, ctx->TL, s, ctx->ph, ctx->st, xa, S.x, xb, S.xf,
+                                        S.b64, S.w, S.dg, S.r, ctx->part(PS_U), from_zero);
         });
         std::swap(xa, xb);
         ++round;
@@ -709,8 +712,10 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
         ctx->prof.resolve(first_stop(ctx, corr));
     }
     record_solve(s, ctx->st, B, corr, round, /*add=*/0, /*fin=*/2);
-    // the corrector uses the FP32 copy of the FP64 solution
-    Ops<float>::cast_in(s, xa, S.x, ctx->NT(), 0.0);
+    // the corrector uses the FP32 copy of the FP64 solution, which the last
+    // refinement wrote to xf: exchange the two buffers' roles for the rest of
+    // the step (x is free again until the next solve writes it)
+    std::swap(S.x, S.xf);
 }
 
 bool audit_on(const pisoc_ctx* ctx) {
