@@ -604,9 +604,11 @@ __global__ void __launch_bounds__(kBlock) k_corr_rhs(
 // p0 from a three-plane one.  The loads of plane kk + 2 (queue heads at
 // kk + 4, resp. kk + 3) are issued after plane kk's work, a plane ahead of
 // their use, and clamped to the planes the chunk needs.  The per-cell
-// arithmetic is corr_rhs_cell, as in k_corr_rhs.
+// arithmetic is corr_rhs_cell, as in k_corr_rhs.  (FP32: at least four
+// wavefronts per SIMD, two blocks per CU, for 2 spilled values; 218 instead
+// of 238 us at 256^3.)
 template <typename T>
-__global__ void __launch_bounds__(kTX * kTY) k_corr_rhs_tiled(
+__global__ void __launch_bounds__(kTX * kTY, sizeof(T) == 4 ? 4 : 2) k_corr_rhs_tiled(
     Phys ph, DevState* st, const T* __restrict__ rn, const T* __restrict__ rk,
     const T* __restrict__ w, const T* __restrict__ hbya, const T* __restrict__ p0,
     T* __restrict__ phiH, T* __restrict__ rvec, T* __restrict__ diag, double* part_u,
