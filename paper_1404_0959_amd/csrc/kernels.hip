@@ -778,6 +778,8 @@ __global__ void __launch_bounds__(kTX * kTY, sizeof(T) == 4 ? 4 : 2) k_corr_rhs_
 // of a solve started from zero) and is not read.  The next inner solve
 // starts from d = 0 without d being written.  x64_new is also written
 // rounded to T (xf): after the last round that is the corrector's solution.
+// store_x = 0 (FROM_ZERO only): x64_new = d exactly, so neither x64_new nor
+// xf is written (d itself serves as the solution).
 template <typename T>
 __device__ inline void refine_cell(const T (&wv)[13], const double (&xv)[7], const T (&dv)[7],
                                    double bP, T dgP, double inv_h2, double& xP, double& r) {
@@ -800,7 +802,7 @@ __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
                                                    T* __restrict__ xf,
                                                    const double* __restrict__ b64,
                                                    const T* __restrict__ w, const T* __restrict__ diag,
-                                                   T* __restrict__ r32, double* part_u) {
+                                                   T* __restrict__ r32, double* part_u, int store_x) {
     MEMBER(ph)
     const double inv_h2 = ph.inv_h2;
     double v[3] = {0.0, 0.0, 0.0};
@@ -815,8 +817,10 @@ __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
     loads_issued();
     double xP, r;
     refine_cell(wv, xv, dv, bP, dgP, inv_h2, xP, r);
-    x64n[P] = xP;
-    xf[P] = (T)xP;
+    if (!FROM_ZERO || store_x) {
+        x64n[P] = xP;
+        xf[P] = (T)xP;
+    }
     const T rT = (T)r;
     r32[P] = rT;
     v[0] += (double)rT * ((double)rT / (double)dgP);
@@ -2464,6 +2468,7 @@ struct TiledRefineFromZero : TiledBase<T> {
     const T* diag;
     double* x64n;
     T *xf, *r32;
+    bool store_x;
     double inv_h2;
     struct Pts { double b; T dg; };
     __device__ void member(const Phys& ph, const DevState*) { inv_h2 = ph.inv_h2; }
@@ -2476,8 +2481,10 @@ struct TiledRefineFromZero : TiledBase<T> {
         cross7(v[1], dv);
         double xP, r;
         refine_cell(v[0], xv, dv, p.b, p.dg, inv_h2, xP, r);
-        stream_st(x64n + P, xP);
-        stream_st(xf + P, (T)xP);
+        if (store_x) {
+            stream_st(x64n + P, xP);
+            stream_st(xf + P, (T)xP);
+        }
         const T rT = (T)r;
         stream_st(r32 + P, rT);
         acc[0] += (double)rT * ((double)rT / (double)p.dg);
@@ -2923,9 +2930,10 @@ template <typename T>
 unsigned Ops<T>::refine(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                         DevState* st, const double* x64, const T* d, double* x64n, T* xf,
                         const double* b64, const T* w, const T* diag, T* r32, double* part_u,
-                        bool from_zero) {
+                        bool from_zero, bool store_x) {
     if (from_zero && TL.nblocks) {
         TiledRefineFromZero<T> k{};
+        k.store_x = store_x;
         k.sf[0] = w;
         k.sf[1] = d;
         k.part = part_u;
@@ -2937,9 +2945,10 @@ unsigned Ops<T>::refine(const Launch& L, const Launch& TL, hipStream_t s, const 
         return tiled_launch<T>(TL, s, ph, st, k);
     }
     if (from_zero)
-        LAUNCH((k_refine<T, true>), L, s, ph, st, x64, d, x64n, xf, b64, w, diag, r32, part_u);
+        LAUNCH((k_refine<T, true>), L, s, ph, st, x64, d, x64n, xf, b64, w, diag, r32, part_u,
+               store_x ? 1 : 0);
     else
-        LAUNCH((k_refine<T, false>), L, s, ph, st, x64, d, x64n, xf, b64, w, diag, r32, part_u);
+        LAUNCH((k_refine<T, false>), L, s, ph, st, x64, d, x64n, xf, b64, w, diag, r32, part_u, 1);
     return L.nblocks;
 }
 template <typename T, int XM>

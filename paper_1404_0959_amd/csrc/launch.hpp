@@ -119,11 +119,12 @@ struct Ops {
                              const T* p0, T* phiH, T* r, T* diag, double* part_u, double* snap_b,
                              double* snap_diag, double* snap_p0, double* b64);
     // from_zero: x64 is zero and not read (first round of a solve from zero);
-    // xf: the new x64n rounded to T (not aliasing d)
+    // xf: the new x64n rounded to T (not aliasing d); store_x = false (with
+    // from_zero): x64n = d exactly, neither x64n nor xf is written
     static unsigned refine(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                            DevState* st, const double* x64, const T* d, double* x64n, T* xf,
                            const double* b64, const T* w, const T* diag, T* r32,
-                           double* part_u, bool from_zero);
+                           double* part_u, bool from_zero, bool store_x);
     // CG iteration k (one kernel); TL: the CG launch of make_spmv_launch
     // (used when TL.nblocks > 0)
     static void pcg_iter(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,

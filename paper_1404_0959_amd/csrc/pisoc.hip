@@ -675,13 +675,20 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
     const int max_rounds = eager ? p.max_refine : ctx->rounds;
     int round = 0;
     unsigned nb_ref = ctx->L.nblocks;   // partials of the last refinement
+    // An eager first round from zero leaves its correction d as the solution
+    // (x64 = d exactly) and stores no copy of it; should a later round follow,
+    // x64 is then made from d.
+    bool sol_in_x = false;
     for (;;) {
         const bool from_zero = round == 0 && !guess;
-        timed(ctx, KC_REFINE, from_zero ? 9 : 11, -1, [&] {
+        const bool store_x = !(from_zero && eager);
+        timed(ctx, KC_REFINE, from_zero ? (store_x ? 9 : 6) : 11, -1, [&] {
             nb_ref = Ops<float>::refine(ctx->L, ctx->TL, s, ctx->ph, ctx->st, xa, S.x, xb, S.xf,
-                                        S.b64, S.w, S.dg, S.r, ctx->part(PS_U), from_zero);
+                                        S.b64, S.w, S.dg, S.r, ctx->part(PS_U), from_zero,
+                                        store_x);
         });
-        std::swap(xa, xb);
+        if (store_x) std::swap(xa, xb);
+        else sol_in_x = true;
         ++round;
         // column 1 (||r64||^2) of the 3 columns written with nb_ref blocks
         finalize_sums(s, ctx->part(PS_U) + nb_ref, nb_ref, B, 1, ctx->st, 0);
@@ -696,6 +703,11 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
                 if (!(h.red[0] <= h.pcg.tol_final * h.pcg.bb) && std::isfinite(h.red[0])) done = false;
             }
             if (done) break;
+        }
+        if (sol_in_x) {
+            // x64 = d before the next round's solve overwrites d
+            Ops<float>::cast_out(s, S.x, xa, ctx->NT(), 0.0);
+            sol_in_x = false;
         }
         set_tol_refine(s, ctx->st, B, p.inner_tol);
         // the inner correction of this round starts from zero (not written)
@@ -714,8 +726,9 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
     record_solve(s, ctx->st, B, corr, round, /*add=*/0, /*fin=*/2);
     // the corrector uses the FP32 copy of the FP64 solution, which the last
     // refinement wrote to xf: exchange the two buffers' roles for the rest of
-    // the step (x is free again until the next solve writes it)
-    std::swap(S.x, S.xf);
+    // the step (x is free again until the next solve writes it); after a
+    // single round from zero it is x itself
+    if (!sol_in_x) std::swap(S.x, S.xf);
 }
 
 bool audit_on(const pisoc_ctx* ctx) {
