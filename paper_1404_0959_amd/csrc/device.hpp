@@ -42,6 +42,7 @@ struct PcgState {
     int32_t maxit;
     int32_t iters;
     int32_t converged;
+    int32_t skip;     // 1: the refinement already meets the tolerance; later rounds do nothing
 };
 
 // Per-member device state, read back by the host after a batch of work.

@@ -804,6 +804,7 @@ __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
                                                    const T* __restrict__ w, const T* __restrict__ diag,
                                                    T* __restrict__ r32, double* part_u, int store_x) {
     MEMBER(ph)
+    if ((st + mem_)->pcg.skip) return;   // converged already: the round does nothing
     const double inv_h2 = ph.inv_h2;
     double v[3] = {0.0, 0.0, 0.0};
     FOR_CELLS(ph)
@@ -891,13 +892,24 @@ __device__ inline void cg_accumulate(double (&v)[CG_COLS], T p, T q, T r, T z, T
 // iterations); beta_k = r_k.z_k / r_{k-1}.z_{k-1}.  Stop at
 // ||r_k||^2 <= tol^2 ||b||^2 or k = maxit; `recorder` (one thread of the
 // member) writes the iteration to the member state.
+// skip (a refinement round after the refinement has converged): the solve
+// stops at k = 0 without touching x.
 struct CgHead {
     double alpha, beta, rr;
-    bool stop;
+    bool stop, skip;
 };
 __device__ inline CgHead cg_head(const Phys& ph, PcgState& g, bool recorder, int mem, int k,
                                  const double* part_in, unsigned nb_in, int fresh, int maxit) {
-    CgHead h{0.0, 0.0, 0.0, false};
+    CgHead h{0.0, 0.0, 0.0, false, false};
+    if (g.skip) {
+        h.stop = h.skip = true;
+        if (recorder) {
+            g.iters = k;
+            g.it_stop = k;
+            g.converged = 1;
+        }
+        return h;
+    }
     // reference ||b||^2: from this system's partials on the first iteration of
     // a fresh solve, else the stored one (later refinement rounds measure
     // against the original right-hand side)
@@ -971,7 +983,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(
     const T alpha = (T)h.alpha, beta = (T)h.beta;
     const CgX<T> xu = cg_x<T, XM>((st + mem_)->pcg, k, h.alpha, xzero);
     if (h.stop) {
-        if (UPD || xzero) {
+        if ((UPD || xzero) && !h.skip) {
             FOR_CELLS(ph)
             x[P] = XE ? xu.two(x[P], pold2[P], pold[P]) : UPD ? xu.one(x[P], pold[P]) : T(0);
             END_CELLS
@@ -1035,7 +1047,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     const size_t nn = (size_t)n * n;
     const CgX<T> xu = cg_x<T, XM>((st + mem_)->pcg, k, h.alpha, xzero);
     if (h.stop) {
-        if (UPD || xzero) {
+        if ((UPD || xzero) && !h.skip) {
 #pragma unroll
             for (int e = 0; e < RPT; ++e) {
                 const size_t c0 = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty + e * kTY);
@@ -1281,7 +1293,7 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     const size_t col = base_ + (size_t)n * (j0 + wv) + (size_t)V * lane;
     const CgX<T> xu = cg_x<T, XM>((st + mem_)->pcg, k, h.alpha, xzero);
     if (h.stop) {
-        if (UPD || xzero) {
+        if ((UPD || xzero) && !h.skip) {
             for (int kk = k0; kk < k1; ++kk) {
                 const size_t Q = col + nn * (size_t)kk;
                 st_v(x, Q, XE    ? xu.two(ld(x, Q), ld(pold2, Q), ld(pold, Q))
@@ -1949,8 +1961,10 @@ __global__ void __launch_bounds__(kBlock) k_sum_affine_sq(Phys ph, const DevStat
 // One block per member: totals of nv partial columns (sums) of member
 // blockIdx.x into st[member].red[off .. off + nv).
 __global__ void __launch_bounds__(kBlock) k_finalize_sums(const double* part, unsigned nbt,
-                                                          int batch, int nv, DevState* st, int off) {
+                                                          int batch, int nv, DevState* st, int off,
+                                                          int honor_skip) {
     const int m = blockIdx.x;
+    if (honor_skip && st[m].pcg.skip) return;   // a skipped refinement round wrote no partials
     for (int c = 0; c < nv; ++c) {
         double t[1];
         reduce_member<1, 0u>(part + (size_t)c * nbt, nbt, batch, m, t);
@@ -2067,15 +2081,21 @@ __global__ void k_record_solve(DevState* st, int batch, int corr, int round, int
 // Tolerance of the next FP32 refinement round of every member from red[0] =
 // ||r64||^2 and the original ||b||^2 (pcg.bb): reduce the current residual
 // to half the requested one, but by no less than the factor tau_min (and at
-// least by 1/2); a member already within p_tol gets a tolerance the solve
-// meets at once.
+// least by 1/2).  A member already within p_tol gets skip = 1: the round's
+// solve stops at k = 0 without touching x, and its refinement and the totals
+// of its partials return at once (x64, xf and red[0] keep the values of the
+// last round that ran).  Rounds beyond convergence occur in captured steps,
+// whose round count is fixed.
 __global__ void k_set_tol_refine(DevState* st, int batch, double tau_min) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= batch) return;
     DevState& d = st[m];
     const double rr = d.red[0], bb = d.pcg.bb;
+    d.pcg.skip = 0;
     if (rr <= d.pcg.tol_final * bb || !(bb > 0.0)) {
+        // done: the round's solve and refinement return at once
         d.pcg.tol2 = 1.0;
+        d.pcg.skip = 1;
         return;
     }
     double tau = 0.5 * sqrt(d.pcg.tol_final * bb / rr);
@@ -2086,7 +2106,9 @@ __global__ void k_set_tol_refine(DevState* st, int batch, double tau_min) {
 // Set the CG tolerance (squared, relative to the reference ||b||) of every member.
 __global__ void k_set_tol(DevState* st, int batch, double tol2) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m < batch) st[m].pcg.tol2 = tol2;
+    if (m >= batch) return;
+    st[m].pcg.tol2 = tol2;
+    st[m].pcg.skip = 0;
 }
 
 // Clear the step flags and the step record of every member (start of a step).
@@ -3156,9 +3178,9 @@ void Ops<T>::sum_affine_sq(const Launch& L, hipStream_t s, const Phys& ph, const
 }
 
 void finalize_sums(hipStream_t s, const double* part, unsigned nbt, int batch, int nv,
-                   DevState* st, int off) {
+                   DevState* st, int off, bool honor_skip) {
     hipLaunchKernelGGL(k_finalize_sums, dim3(batch), dim3(64, 4), 0, s, part, nbt, batch, nv, st,
-                       off);
+                       off, honor_skip ? 1 : 0);
 }
 void sum_partials(hipStream_t s, const double* part, unsigned nb, double* dst) {
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64, 4), 0, s, part, nb, dst);

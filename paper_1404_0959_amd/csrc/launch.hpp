@@ -191,9 +191,10 @@ struct Ops {
 };
 
 // Per member: totals of nv partial columns (written by a launch of nbt blocks
-// over `batch` members) into st[m].red[off ..].
+// over `batch` members) into st[m].red[off ..]; honor_skip: not for a member
+// whose refinement round was skipped (pcg.skip).
 void finalize_sums(hipStream_t s, const double* part, unsigned nbt, int batch, int nv,
-                   DevState* st, int off);
+                   DevState* st, int off, bool honor_skip = false);
 // Total of nb partials (one column) into dst[0].
 void sum_partials(hipStream_t s, const double* part, unsigned nb, double* dst);
 // Per member: end-of-step mass budget and flags.

@@ -691,7 +691,7 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
         else sol_in_x = true;
         ++round;
         // column 1 (||r64||^2) of the 3 columns written with nb_ref blocks
-        finalize_sums(s, ctx->part(PS_U) + nb_ref, nb_ref, B, 1, ctx->st, 0);
+        finalize_sums(s, ctx->part(PS_U) + nb_ref, nb_ref, B, 1, ctx->st, 0, true);
         if (round >= max_rounds) break;
         if (eager) {
             if ((*err = sync_state(ctx)) != PISOC_OK) return;
