@@ -842,14 +842,14 @@ __global__ void __launch_bounds__(kBlock) k_refine(Phys ph, DevState* st,
 // and the direction p_k = z_k + beta_k p_{k-1}; iteration 0 takes p_0 = z_0.
 // Then q_k = M p_k with the face coefficients K = I4(w) formed on the fly; the
 // kernel stores r_k, p_k and q_k and writes the partial sums from which the
-// next iteration takes its scalars (cg_head).  x is updated every other
-// iteration: an even k >= 2 applies x += alpha_{k-2} p_{k-2} + alpha_{k-1}
-// p_{k-1} (p_{k-1} is read anyway), an odd k leaves x alone; the stop
-// iteration adds what is still due (one term at an odd k, two at an even
-// k).  The rounding is that of adding the terms one iteration at a time.  The iterates
-// are those of textbook PCG; r_k.z_k and ||r_k||^2 are expanded from sums of
-// iteration k-1 instead of being summed over r_k, so one global reduction per
-// iteration suffices.  r and q alternate between two buffers (iteration k
+// next iteration takes its scalars (cg_head).  The iterates are those of
+// textbook PCG; r_k.z_k and ||r_k||^2 are expanded from sums of iteration
+// k-1 instead of being summed over r_k, so one global reduction per
+// iteration suffices.  x is updated every other iteration: an even k >= 2
+// applies x += alpha_{k-2} p_{k-2} + alpha_{k-1} p_{k-1} (p_{k-1} is read
+// anyway), an odd k leaves x alone, and the stop iteration adds what is
+// still due (one term at an odd k, two at an even k), with the rounding of
+// adding the terms one iteration at a time.  r and q alternate between two buffers (iteration k
 // reads the k-1 values on the stencil while writing its own), p rotates
 // through three (an even k also reads p_{k-2}).  With xzero (the solve
 // started from x = 0, not written) the first write of x sets it: at k = 2,
@@ -891,9 +891,9 @@ __device__ inline void cg_accumulate(double (&v)[CG_COLS], T p, T q, T r, T z, T
 // each one step from sums over the stored r_{k-1} (no drift accumulates over
 // iterations); beta_k = r_k.z_k / r_{k-1}.z_{k-1}.  Stop at
 // ||r_k||^2 <= tol^2 ||b||^2 or k = maxit; `recorder` (one thread of the
-// member) writes the iteration to the member state.
-// skip (a refinement round after the refinement has converged): the solve
-// stops at k = 0 without touching x.
+// member) writes the iteration to the member state.  With pcg.skip (a
+// refinement round after the refinement has converged) the solve stops at
+// k = 0 without touching x.
 struct CgHead {
     double alpha, beta, rr;
     bool stop, skip;
