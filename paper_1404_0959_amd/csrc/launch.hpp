@@ -16,7 +16,7 @@ struct Launch {
     unsigned nblocks;   // all members
     int cz;             // cells per thread along z
     int nz;             // blocks per member along z
-    int v = 0;          // CG first half: cells per lane along x of the full-row form (0: tiles)
+    int v = 0;          // CG kernel: cells per lane along x of the full-row form (0: tiles)
 };
 
 constexpr int kTargetBlocks = 2048;
@@ -36,7 +36,7 @@ Launch make_launch_shaped(int n, int batch, int bx, int cz);
 // x and its x halo wraps onto itself.
 Launch make_tiled_launch(int n, int batch = 1);
 
-// Launch of the CG first half for fields of elem_bytes per value.  For
+// Launch of the CG kernel for fields of elem_bytes per value.  For
 // n = 64 kRowCells and FP32: the full-row form, blocks of kRowWaves
 // wavefronts each owning one x-row (kRowCells cells per lane), about
 // kRowBlocks blocks per member (v = kRowCells; in FP64 its registers would

@@ -208,7 +208,7 @@ struct pisoc_ctx {
     bool cfl_ready = false;
     unsigned nb_cfl = 0, nb_cfl_next = 0;
     const double* cfl_part = nullptr;
-    Launch TS;      // tiled launch of the CG first half (nblocks = 0: none)
+    Launch TS;      // tiled launch of the CG kernel (nblocks = 0: none)
     DevState* st;
     DevState* hst = nullptr;  // pinned host copy (batch entries)
     double* partials;

@@ -87,7 +87,7 @@ def test_helm_apply_parity(P, ora, n):
 
 @pytest.mark.parametrize("n", [16, 40, 128, 256])
 def test_helm_solve_parity(P, ora, n):
-    """128 and 256 run the 64 x 8 tiled CG first half (FP64)."""
+    """128 and 256 run the 64 x 8 tiled CG kernel (FP64)."""
     import torch
     rng = np.random.default_rng(100 + n)
     h = 2 * math.pi / n
@@ -175,7 +175,7 @@ def test_step_parity_hit128_tiled(P, ora, n):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_tiled_kernels_match_gathered(P, monkeypatch, precision, n):
     """At n = 64 and 128 the stencil kernels run as tiled z-marches (the generic k_tiled
-    driver, the tiled corrector set-up, momentum sweep and CG first half); with
+    driver, the tiled corrector set-up, momentum sweep and CG kernel); with
     PISOC_UNTILED=1 the same step runs the gathered kernels. Both call the same
     cell arithmetic; only reduction order differs, so the CG iteration counts
     agree and the fields agree to rounding (FP64: 1e-11 of the spread; FP32:
