@@ -117,9 +117,10 @@ def timed_run(P, torch, case, prec, args, guess=None):
 
 def ensemble_run(P, torch, args, weights):
     """The mixed-size ensemble (32^3, 48^3, 64^3 in the ratio 2:1:1, Mach from
-    {0.2, 0.5}, Stokes U[0.05, 0.5]; FP32 + learned guess) stepped by replaying
-    one captured graph per step after the launch-shape autotuner, against the
-    same members stepped one after another as single grids."""
+    {0.2, 0.5}, Stokes U[0.05, 0.5]; FP32 + learned guess under the audit, whose
+    verdict per size class the captured step keeps) stepped by replaying one
+    captured graph per step after the launch-shape autotuner, against the same
+    members stepped one after another as single grids."""
     import tempfile
 
     import numpy as np
@@ -129,7 +130,7 @@ def ensemble_run(P, torch, args, weights):
     cells = sum(c.n ** 3 for c in cases)
     common = dict(p_tol=args.p_tol, cfl=0.5, n_corr=2, n_mom_sweeps=4, n_dust_sweeps=4)
     fast = dict(precision=P.FP32_REFINED, inner_tol=args.inner_tol, guess=P.GUESS_LEARNED,
-                guess_weights=weights.data_ptr(), **common)
+                guess_weights=weights.data_ptr(), guess_audit=args.guess_audit, **common)
     out = {"members": len(cases), "cells": cells,
            "sizes": {str(n): sum(1 for c in cases if c.n == n) for n in sorted({c.n for c in cases})}}
 
@@ -158,7 +159,8 @@ def ensemble_run(P, torch, args, weights):
     out["status"] = st_holder["st"]
     out["max_relres"] = max(max(i["pcg_relres"]) for i in st_holder["info"])
     out["pcg_iters_mean"] = float(np.mean([np.mean(i["pcg_iters"]) for i in st_holder["info"]]))
-    out["classes"] = [{k: c[k] for k in ("n", "members", "block", "cells_z", "caps", "rounds")}
+    out["classes"] = [{k: c[k] for k in ("n", "members", "block", "cells_z", "caps", "rounds",
+                                         "guess_mask")}
                       for c in E.classes()]
     log(f"ensemble graph: {out['ms_per_step']:.3f} ms/step, {out['value']:.4e} cell-steps/s")
 

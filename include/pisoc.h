@@ -105,7 +105,9 @@ typedef struct {
                                   without it) exceed its own cost in CG-iteration
                                   equivalents (timed with events), trying the other choice
                                   once every k steps (PISOC_FLAG_GUESS_SKIPPED marks steps
-                                  that went without it) */
+                                  that went without it).  Eager ensemble steps audit the
+                                  same way; a captured ensemble step keeps the verdict
+                                  its graph was built with (without the periodic trial) */
 } pisoc_params;
 
 typedef struct {
@@ -209,7 +211,9 @@ int32_t pisoc_profile_read(const pisoc_ctx* ctx, pisoc_kernel_stat* h_out, int32
  * needed, +25% + 2) of which every launch after a member's own convergence
  * returns at once, the FP32 refinement runs a fixed number of rounds, and the
  * step is committed on the device.  The first captured call begins with one
- * eager step that measures those iterations.  A solve that reaches its cap
+ * eager step that measures those iterations (two where a class audits its
+ * learned guess and has not yet measured both choices; a call too short for
+ * them returns before capturing, and the next one goes on).  A solve that reaches its cap
  * without converging flags PISOC_FLAG_PCG_MAXIT (status
  * PISOC_WARN_NOT_CONVERGED, the state has advanced); the caps then grow and the
  * graph is captured again on the next call.  A diverged member cannot be rolled
@@ -225,6 +229,8 @@ typedef struct {
     int32_t caps[PISOC_MAX_CORR];       /* captured step: CG iterations of each first solve */
     int32_t cap_later;                  /* ... of each later refinement round */
     int32_t rounds;                     /* ... FP64 refinement rounds (FP32_REFINED) */
+    int32_t guess_mask;                 /* ... bit c set: corrector c's solve starts from
+                                           the learned guess */
 } pisoc_ens_class;
 
 /* Workspace for the ensemble (0 if the members are invalid); 256-byte aligned. */

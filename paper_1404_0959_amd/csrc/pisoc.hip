@@ -754,6 +754,23 @@ void audit_decide(pisoc_ctx* ctx) {
     }
 }
 
+// The choice a captured step is built with: the audit's current verdict for
+// each corrector, without the periodic probe (a choice not measured yet
+// counts as paying).
+void audit_decide_capture(pisoc_ctx* ctx) {
+    auto& A = ctx->audit;
+    for (int c = 0; c < ctx->prm.n_corr; ++c)
+        A.use[c] = A.it_guess[c] < 0.0 || A.it_zero[c] < 0.0 ||
+                   A.it_zero[c] - A.it_guess[c] > std::max(A.cost, 0.0);
+}
+
+// Both choices measured for every corrector (the capture can take a verdict).
+bool audit_measured(const pisoc_ctx* ctx) {
+    for (int c = 0; c < ctx->prm.n_corr; ++c)
+        if (ctx->audit.it_guess[c] < 0.0 || ctx->audit.it_zero[c] < 0.0) return false;
+    return true;
+}
+
 // After the step's last synchronisation: fold its iterations and timings in.
 void audit_update(pisoc_ctx* ctx) {
     auto& A = ctx->audit;
@@ -786,9 +803,12 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
     ctx->cfl_ready = false;
     ctx->nb_cfl_next = 0;
     enqueue_front<T>(ctx, S, cfl_ready);
+    // with the audit on, an eager step takes this step's decision and a
+    // captured one the verdict it was built with (audit_decide_capture)
     const bool audit = eager && audit_on(ctx);
     for (int corr = 0; corr < p.n_corr; ++corr) {
-        const bool guess = p.guess == PISOC_GUESS_LEARNED && (!audit || ctx->audit.use[corr]);
+        const bool guess =
+            p.guess == PISOC_GUESS_LEARNED && (!audit_on(ctx) || ctx->audit.use[corr]);
         if (audit && guess) (void)hipEventRecord(ctx->audit.ev[corr][0], s);
         enqueue_corr_setup<T>(ctx, S, corr, guess);
         if (audit && guess) (void)hipEventRecord(ctx->audit.ev[corr][1], s);
@@ -1362,6 +1382,8 @@ void set_caps(pisoc_ctx* ctx, const int* first, int later, int rounds) {
 // exec[0], then, with the buffers rotated, into exec[1]; rotations restored.
 pisoc_status build_graphs(pisoc_ens* e) {
     drop_graphs(e);
+    for (pisoc_ctx* ctx : e->cls)
+        if (audit_on(ctx)) audit_decide_capture(ctx);
     for (int par = 0; par < 2; ++par) {
         hipGraph_t g = nullptr;
         if (hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -1647,9 +1669,18 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
     pisoc_status worst = PISOC_OK;
     std::vector<pisoc_step_info> rec(e->count);
     if (mode == PISOC_ENS_EAGER || !e->built) {
-        // eager steps (the first captured call begins with one: it measures
-        // the CG iterations that size the graph's caps)
-        const int k = mode == PISOC_ENS_EAGER ? n_steps : 1;
+        // eager steps.  A captured call begins with one, which measures the CG
+        // iterations that size the graph's caps, or with two where the
+        // learned-guess audit has yet to measure both of its choices (the
+        // capture takes its verdict); the graph is built once that is done.
+        int k = n_steps;
+        if (mode == PISOC_ENS_GRAPH) {
+            int need = 1;
+            for (pisoc_ctx* ctx : e->cls)
+                if (audit_on(ctx) && !audit_measured(ctx))
+                    need = std::max(need, ctx->audit.it_guess[0] < 0.0 ? 2 : 1);
+            k = std::min(n_steps, need);
+        }
         for (int i = 0; i < k; ++i) {
             for (size_t c = 0; c < e->cls.size(); ++c) {
                 pisoc_ctx* ctx = e->cls[c];
@@ -1680,7 +1711,14 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
             if (h_info) std::copy(rec.begin(), rec.end(), h_info);
             return worst;
         }
-        n_steps -= 1;
+        n_steps -= k;
+        bool ready = true;
+        for (pisoc_ctx* ctx : e->cls)
+            if (audit_on(ctx) && !audit_measured(ctx)) ready = false;
+        if (!ready) {
+            if (h_info) std::copy(rec.begin(), rec.end(), h_info);
+            return worst;
+        }
         pisoc_status st = build_graphs(e);
         if (st != PISOC_OK) return st;
     }
@@ -1718,10 +1756,14 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
             int first[PISOC_MAX_CORR] = {0, 0, 0, 0};
             int later = 0;
             bool regrow = false;
+            int skipped = 0;
+            if (audit_on(ctx))
+                for (int q = 0; q < ctx->prm.n_corr; ++q)
+                    skipped |= ctx->audit.use[q] ? 0 : PISOC_FLAG_GUESS_SKIPPED;
             for (int j = 0; j < ctx->batch; ++j) {
                 const DevState& h = ctx->hst[j];
                 fill_info(ctx, h, true, &rec[e->members[c][j]]);
-                rec[e->members[c][j]].flags |= h.flags_acc;
+                rec[e->members[c][j]].flags |= h.flags_acc | skipped;
                 worst = combine_status(worst, flag_status(h.flags_acc));
                 if (member_bad(ctx, h) || (h.flags_acc & (PISOC_FLAG_NONFINITE | PISOC_FLAG_RHO_NONPOS)))
                     bad = true;
@@ -1806,6 +1848,9 @@ pisoc_status pisoc_ens_class_info(const pisoc_ens* e, int32_t cls, pisoc_ens_cla
     o.rounds = ctx->rounds;
     o.cap_later = ctx->cap_later;
     for (int c = 0; c < PISOC_MAX_CORR; ++c) o.caps[c] = ctx->caps[c];
+    for (int c = 0; c < ctx->prm.n_corr; ++c)
+        if (ctx->prm.guess == PISOC_GUESS_LEARNED && (!audit_on(ctx) || ctx->audit.use[c]))
+            o.guess_mask |= 1 << c;
     *h_out = o;
     return PISOC_OK;
 }

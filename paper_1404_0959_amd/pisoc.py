@@ -81,7 +81,8 @@ class Stats(C.Structure):
 class EnsClass(C.Structure):
     _fields_ = [("n", C.c_int32), ("members", C.c_int32), ("block_x", C.c_int32),
                 ("block_y", C.c_int32), ("cells_z", C.c_int32), ("blocks", C.c_int32),
-                ("caps", C.c_int32 * MAX_CORR), ("cap_later", C.c_int32), ("rounds", C.c_int32)]
+                ("caps", C.c_int32 * MAX_CORR), ("cap_later", C.c_int32), ("rounds", C.c_int32),
+                ("guess_mask", C.c_int32)]
 
 
 class KernelStat(C.Structure):
@@ -410,7 +411,7 @@ class Ensemble:
                 raise PisocError(st, self.last_error())
             out.append(dict(n=e.n, members=e.members, block=(e.block_x, e.block_y),
                             cells_z=e.cells_z, blocks=e.blocks, caps=list(e.caps),
-                            cap_later=e.cap_later, rounds=e.rounds))
+                            cap_later=e.cap_later, rounds=e.rounds, guess_mask=e.guess_mask))
         return out
 
     def fields(self, m, which):

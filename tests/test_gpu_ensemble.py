@@ -7,8 +7,8 @@ reduction runs over the member's own blocks in the same order); a member agrees
 with the FP64 oracle to the whole-step parity bar; the captured-graph mode
 reproduces eager mode (FP64: identical solves while the iteration caps hold;
 FP32 + learned guess: within the pressure tolerance, each solve at
-||r|| <= p_tol ||b||, the gas and dust mass conserved to round-off); the
-autotuner's cache round-trips.
+||r|| <= p_tol ||b||, the gas and dust mass conserved to round-off, an audited
+guess applied per its captured verdict); the autotuner's cache round-trips.
 """
 import json
 
@@ -143,6 +143,48 @@ def test_graph_fp32_learned(P):
         assert not ib[m]["flags"] & P.FLAG_PCG_MAXIT
         assert abs(sb_stats[m]["mass_gas"] - m0[m]) <= 1e-10 * m0[m]
         assert abs(sb_stats[m]["mass_p"][0] - p0[m]) <= 1e-7 * p0[m]
+        ua = a.get(m, P.FIELD_U).cpu().numpy()
+        ub = b.get(m, P.FIELD_U).cpu().numpy()
+        assert np.max(np.abs(ua - ub)) <= 1e-4 * np.max(np.abs(ua)), m
+
+
+def test_graph_keeps_audit_verdict(P):
+    """Audited learned guess in captured mode: the first captured call is too
+    short to capture (the audit has measured only the guess), the second
+    measures the zero guess and captures; the captured steps then apply each
+    class's verdict (PISOC_FLAG_GUESS_SKIPPED exactly where a corrector goes
+    without the guess), meet the tolerance, conserve mass and stay within the
+    solver tolerance of the audited eager run."""
+    from paper_1404_0959_amd.learn import load_weights
+    w = load_weights()
+    cs = cases()
+    kw = dict(p_tol=1e-6, precision=P.FP32_REFINED, inner_tol=1e-3, guess=P.GUESS_LEARNED,
+              guess_weights=w.data_ptr(), guess_audit=8)
+    a = P.Ensemble(cs, **kw)
+    b = P.Ensemble(cs, **kw)
+    m0 = [s["mass_gas"] for s in b.stats()]
+    sb, ib = b.step(1, mode=P.ENS_GRAPH)
+    assert b.steps_done == 1
+    assert all(not i["flags"] & P.FLAG_GUESS_SKIPPED for i in ib)
+    sb, ib = b.step(1, mode=P.ENS_GRAPH)
+    assert b.steps_done == 2
+    assert all(i["flags"] & P.FLAG_GUESS_SKIPPED for i in ib)
+    sb, ib = b.step(3, mode=P.ENS_GRAPH)
+    assert b.steps_done == 5
+    sa, ia = a.step(5, mode=P.ENS_EAGER)
+    assert sa in (P.OK, P.WARN_GUESS_FALLBACK) and sb in (P.OK, P.WARN_GUESS_FALLBACK)
+    full = (1 << b.prms[0].n_corr) - 1
+    mask = {}
+    for cl in b.classes():
+        assert 0 <= cl["guess_mask"] <= full
+        mask[cl["n"]] = cl["guess_mask"]
+    print("verdicts", mask)
+    st = b.stats()
+    for m, c in enumerate(cs):
+        assert bool(ib[m]["flags"] & P.FLAG_GUESS_SKIPPED) == (mask[c.n] != full), (m, ib[m])
+        assert max(ib[m]["pcg_relres"]) <= 1e-6, ib[m]
+        assert not ib[m]["flags"] & P.FLAG_PCG_MAXIT
+        assert abs(st[m]["mass_gas"] - m0[m]) <= 1e-10 * m0[m]
         ua = a.get(m, P.FIELD_U).cpu().numpy()
         ub = b.get(m, P.FIELD_U).cpu().numpy()
         assert np.max(np.abs(ua - ub)) <= 1e-4 * np.max(np.abs(ua)), m
