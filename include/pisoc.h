@@ -206,7 +206,8 @@ int32_t pisoc_profile_read(const pisoc_ctx* ctx, pisoc_kernel_stat* h_out, int32
  * calls that step or read it synchronise them.
  *
  * PISOC_ENS_EAGER steps like pisoc_step, per class.  PISOC_ENS_GRAPH replays
- * one captured HIP graph per step for the whole ensemble: each pressure solve
+ * one captured HIP graph per step for each size class, on the class's stream
+ * (the classes' replays overlap): each pressure solve
  * runs a fixed number of CG iterations (sized from the iterations the members
  * needed, +25% + 2) of which every launch after a member's own convergence
  * returns at once, the FP32 refinement runs a fixed number of rounds, and the

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1345,11 +1346,9 @@ struct pisoc_ens {
     std::vector<pisoc_ctx*> cls;                  // one context per grid size
     std::vector<std::pair<int, int>> where;       // member -> (class, index in class)
     std::vector<std::vector<int>> members;        // class -> member ids
-    std::vector<hipStream_t> streams;             // one per class (graph branches)
-    hipStream_t stream = nullptr;                 // the ensemble's own stream (capture, replay)
-    hipGraphExec_t exec[2] = {nullptr, nullptr};  // per buffer parity
-    hipEvent_t fork = nullptr;
-    std::vector<hipEvent_t> join;
+    std::vector<hipStream_t> streams;             // one per class
+    // captured step of each class (replayed on its own stream), per buffer parity
+    std::vector<std::array<hipGraphExec_t, 2>> exec;
     int parity = 0;
     bool built = false;
     int64_t steps = 0;
@@ -1359,11 +1358,12 @@ struct pisoc_ens {
 namespace {
 
 void drop_graphs(pisoc_ens* e) {
-    for (auto& g : e->exec)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
+    for (auto& pair : e->exec)
+        for (auto& g : pair)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
     e->built = false;
 }
 
@@ -1378,43 +1378,38 @@ void set_caps(pisoc_ctx* ctx, const int* first, int later, int rounds) {
     ctx->rounds = std::max(ctx->rounds, std::max(1, std::min(rounds + 1, ctx->prm.max_refine)));
 }
 
-// Capture one step of every class (fork/join over the class streams) into
-// exec[0], then, with the buffers rotated, into exec[1]; rotations restored.
+// Capture one step of each class on its own stream into exec[c][0], then,
+// with the buffers rotated, into exec[c][1]; rotations restored.  The classes
+// are independent graphs so that their replays on the class streams overlap.
 pisoc_status build_graphs(pisoc_ens* e) {
     drop_graphs(e);
+    e->exec.assign(e->cls.size(), {nullptr, nullptr});
     for (pisoc_ctx* ctx : e->cls)
         if (audit_on(ctx)) audit_decide_capture(ctx);
     for (int par = 0; par < 2; ++par) {
-        hipGraph_t g = nullptr;
-        if (hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-            e->err = "hipStreamBeginCapture failed";
-            return PISOC_ERR_HIP;
-        }
-        hipError_t rc = hipEventRecord(e->fork, e->stream);
-        pisoc_status st = PISOC_OK;
-        for (size_t c = 0; c < e->cls.size() && rc == hipSuccess && st == PISOC_OK; ++c) {
+        for (size_t c = 0; c < e->cls.size(); ++c) {
             pisoc_ctx* ctx = e->cls[c];
-            rc = hipStreamWaitEvent(ctx->stream, e->fork, 0);
-            if (rc != hipSuccess) break;
-            st = ctx->prm.precision == PISOC_FP64 ? enqueue_step<double>(ctx, false)
-                                                  : enqueue_step<float>(ctx, false);
-            if (st != PISOC_OK) break;
-            rc = hipEventRecord(e->join[c], ctx->stream);
-            if (rc == hipSuccess) rc = hipStreamWaitEvent(e->stream, e->join[c], 0);
-        }
-        const hipError_t rc_end = hipStreamEndCapture(e->stream, &g);
-        if (rc != hipSuccess || st != PISOC_OK || rc_end != hipSuccess || !g) {
-            if (g) (void)hipGraphDestroy(g);
-            e->err = std::string("graph capture failed: ") +
-                     hipGetErrorString(rc != hipSuccess ? rc : rc_end);
-            return PISOC_ERR_HIP;
-        }
-        rc = hipGraphInstantiate(&e->exec[par], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (rc != hipSuccess) {
-            e->exec[par] = nullptr;
-            e->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(rc);
-            return PISOC_ERR_HIP;
+            hipGraph_t g = nullptr;
+            if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                e->err = "hipStreamBeginCapture failed";
+                return PISOC_ERR_HIP;
+            }
+            const pisoc_status st = ctx->prm.precision == PISOC_FP64 ? enqueue_step<double>(ctx, false)
+                                                                     : enqueue_step<float>(ctx, false);
+            const hipError_t rc_end = hipStreamEndCapture(ctx->stream, &g);
+            if (st != PISOC_OK || rc_end != hipSuccess || !g) {
+                if (g) (void)hipGraphDestroy(g);
+                e->err = std::string("graph capture failed: ") +
+                         (st != PISOC_OK ? ctx->err : std::string(hipGetErrorString(rc_end)));
+                return st != PISOC_OK ? st : PISOC_ERR_HIP;
+            }
+            const hipError_t rc = hipGraphInstantiate(&e->exec[c][par], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (rc != hipSuccess) {
+                e->exec[c][par] = nullptr;
+                e->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(rc);
+                return PISOC_ERR_HIP;
+            }
         }
         for (pisoc_ctx* ctx : e->cls) rotate(ctx);
     }
@@ -1604,12 +1599,6 @@ pisoc_status pisoc_ens_init(const pisoc_params* members, int32_t count, void* d_
     e->members = classes;
     e->where.assign(count, {0, 0});
     pisoc_status st = PISOC_OK;
-    if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess) {
-        e->stream = nullptr;
-        st = PISOC_ERR_HIP;
-    }
-    if (st == PISOC_OK && hipEventCreateWithFlags(&e->fork, hipEventDisableTiming) != hipSuccess)
-        st = PISOC_ERR_HIP;
     // class streams wait for the caller's stream (the inputs) before the set-up
     hipEvent_t ready = nullptr;
     if (st == PISOC_OK &&
@@ -1618,17 +1607,11 @@ pisoc_status pisoc_ens_init(const pisoc_params* members, int32_t count, void* d_
         st = PISOC_ERR_HIP;
     for (size_t c = 0; c < classes.size() && st == PISOC_OK; ++c) {
         hipStream_t s = nullptr;
-        hipEvent_t j = nullptr;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
             st = PISOC_ERR_HIP;
             break;
         }
         e->streams.push_back(s);
-        if (hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
-            st = PISOC_ERR_HIP;
-            break;
-        }
-        e->join.push_back(j);
         if (hipStreamWaitEvent(s, ready, 0) != hipSuccess) {
             st = PISOC_ERR_HIP;
             break;
@@ -1723,19 +1706,16 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
         if (st != PISOC_OK) return st;
     }
     if (n_steps > 0) {
-        // the graph runs on the ensemble's stream: earlier work on the class
-        // streams (set-up, eager steps, copies) must be complete
-        for (pisoc_ctx* ctx : e->cls)
-            if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
-                e->err = "stream synchronisation failed";
-                return PISOC_ERR_HIP;
-            }
-        for (pisoc_ctx* ctx : e->cls) clear_acc(e->stream, ctx->st, ctx->batch);
+        // each class's graph runs on the class stream, after the work already
+        // there (set-up, eager steps, copies)
+        for (pisoc_ctx* ctx : e->cls) clear_acc(ctx->stream, ctx->st, ctx->batch);
         for (int i = 0; i < n_steps; ++i) {
-            const hipError_t rc = hipGraphLaunch(e->exec[e->parity], e->stream);
-            if (rc != hipSuccess) {
-                e->err = std::string("hipGraphLaunch: ") + hipGetErrorString(rc);
-                return PISOC_ERR_HIP;
+            for (size_t c = 0; c < e->cls.size(); ++c) {
+                const hipError_t rc = hipGraphLaunch(e->exec[c][e->parity], e->cls[c]->stream);
+                if (rc != hipSuccess) {
+                    e->err = std::string("hipGraphLaunch: ") + hipGetErrorString(rc);
+                    return PISOC_ERR_HIP;
+                }
             }
             e->parity ^= 1;
             for (pisoc_ctx* ctx : e->cls) {
@@ -1743,10 +1723,6 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
                 ctx->steps += 1;
             }
             e->steps += 1;
-        }
-        if (hipStreamSynchronize(e->stream) != hipSuccess) {
-            e->err = "stream synchronisation failed";
-            return PISOC_ERR_HIP;
         }
         pisoc_status st = ens_sync(e);
         if (st != PISOC_OK) return st;
@@ -1882,9 +1858,6 @@ void pisoc_ens_destroy(pisoc_ens* e) {
     drop_graphs(e);
     for (pisoc_ctx* ctx : e->cls) free_ctx(ctx);
     for (hipStream_t s : e->streams) (void)hipStreamDestroy(s);
-    for (hipEvent_t j : e->join) (void)hipEventDestroy(j);
-    if (e->fork) (void)hipEventDestroy(e->fork);
-    if (e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
 }
 
