@@ -182,8 +182,12 @@ const char* pisoc_status_string(pisoc_status st);
  * When enabled, every kernel launch of pisoc_step is bracketed by HIP events
  * on the context's stream and attributed to its kernel class, together with
  * its algorithmic HBM bytes (each field word the kernel must read or write
- * once).  CG launches that return at once because the solve has converged are
- * not counted.  Enabling resets the counters. */
+ * once).  The back-to-back CG launches issued between two host waits of a
+ * solve are bracketed together instead, and their time goes to the working
+ * ones: CG launches that return at once because the solve has converged are
+ * not counted as launches (their few microseconds stay in the time).  The
+ * events are timing-only (no system-scope fence).  Enabling resets the
+ * counters. */
 #define PISOC_MAX_KSTATS 24
 typedef struct {
     char name[32];

@@ -87,14 +87,21 @@ struct Prof {
     bool on = false;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
-    struct Rec { int cls; size_t ea, eb; double bytes; int k; };
+    // k: CG iteration (-1 for other kernels); stop_bytes: what the CG launch
+    // moves if the solve stops at it (the last x update)
+    struct Rec { int cls; size_t ea, eb; double bytes; int k; double stop_bytes; };
     std::vector<Rec> pending;
     pisoc_kernel_stat stat[KC_COUNT];
 
+    // timing-only events: recorded without the system-scope fence (its L2
+    // write-back and invalidation would be charged to the bracketed kernel
+    // and cool the cache for the next one); their times are read after a
+    // stream synchronisation
     size_t take() {
         if (used == pool.size()) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return (size_t)-1;
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+                return (size_t)-1;
             pool.push_back(e);
         }
         return used++;
@@ -106,15 +113,34 @@ struct Prof {
         pending.clear();
         used = 0;
     }
-    // Attribute completed launches; CG launches with k >= it_stop returned at once.
+    // Attribute completed launches.  CG launch k < it_stop is an iteration;
+    // k == it_stop made the solve's last x update (its stop_bytes); later ones
+    // returned at once.  Records sharing one pair of events are a run of
+    // back-to-back launches of one class: the run's time goes to its working
+    // launches (those that returned at once inside it are charged to them).
     void resolve(int it_stop) {
-        for (const Rec& r : pending) {
-            if (r.k >= 0 && r.k >= it_stop) continue;
+        for (size_t i = 0; i < pending.size();) {
+            const Rec& r0 = pending[i];
+            size_t j = i;
+            int working = 0;
+            double bytes = 0.0;
+            for (; j < pending.size() && pending[j].ea == r0.ea && pending[j].eb == r0.eb; ++j) {
+                const Rec& r = pending[j];
+                if (r.k < 0 || r.k < it_stop) {
+                    working += 1;
+                    bytes += r.bytes;
+                } else if (r.k == it_stop && r.stop_bytes > 0.0) {
+                    working += 1;
+                    bytes += r.stop_bytes;
+                }
+            }
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, pool[r.ea], pool[r.eb]) != hipSuccess) continue;
-            stat[r.cls].launches += 1;
-            stat[r.cls].ms += ms;
-            stat[r.cls].bytes += r.bytes;
+            if (working > 0 && hipEventElapsedTime(&ms, pool[r0.ea], pool[r0.eb]) == hipSuccess) {
+                stat[r0.cls].launches += working;
+                stat[r0.cls].ms += ms;
+                stat[r0.cls].bytes += bytes;
+            }
+            i = j;
         }
         pending.clear();
         used = 0;
@@ -278,7 +304,7 @@ void timed(pisoc_ctx* ctx, int cls, double words, int k, F&& launch) {
     (void)hipEventRecord(P.pool[a], ctx->stream);
     launch();
     (void)hipEventRecord(P.pool[b], ctx->stream);
-    P.pending.push_back({cls, a, b, words * (double)ctx->es * (double)ctx->NT(), k});
+    P.pending.push_back({cls, a, b, words * (double)ctx->es * (double)ctx->NT(), k, 0.0});
 }
 
 pisoc_status sync_state(pisoc_ctx* ctx) {
@@ -339,42 +365,62 @@ pisoc_status run_pcg(pisoc_ctx* ctx, const CgVecs<T>& v, bool fresh, int iters, 
     using O = Ops<T>;
     const int maxit = cap > 0 ? std::min(cap, ctx->prm.p_maxit) : ctx->prm.p_maxit;
     const unsigned nb_cg = ctx->TS.nblocks ? ctx->TS.nblocks : ctx->L.nblocks;
-    auto iter = [&](int k) {
-        // words: r, diag, w read, p, q written; from k = 1 also q, p_old read and r written;
-        // at even k >= 2 also p_{k-2} read and x updated
-        timed(ctx, KC_PCG_SPMV, k == 0 ? 5.0 : (k & 1) ? 8.0 : 11.0, k, [&] {
-            CgArgs<T> a;
-            a.rin = v.r[k == 0 ? 0 : (k + 1) & 1];
-            a.rout = v.r[k & 1];
-            a.diag = v.diag;
-            a.w = v.w;
-            a.pold = v.p[(k + 2) % 3];
-            a.pold2 = v.p[(k + 1) % 3];
-            a.pnew = v.p[k % 3];
-            a.qold = v.q[(k + 1) & 1];
-            a.q = v.q[k & 1];
-            a.x = v.x;
-            a.part_in = k == 0 ? ctx->part(PS_U) : ctx->part(PS_CG + kCgCols * ((k + 1) & 1));
-            a.nb_in = k == 0 ? nb_first : nb_cg;
-            a.part_out = ctx->part(PS_CG + kCgCols * (k & 1));
-            a.fresh = fresh ? 1 : 0;
-            a.maxit = maxit;
-            a.xzero = xzero ? 1 : 0;
-            O::pcg_iter(ctx->L, ctx->TS, ctx->stream, ctx->ph, ctx->st, k, a);
-        });
+    auto launch = [&](int k) {
+        CgArgs<T> a;
+        a.rin = v.r[k == 0 ? 0 : (k + 1) & 1];
+        a.rout = v.r[k & 1];
+        a.diag = v.diag;
+        a.w = v.w;
+        a.pold = v.p[(k + 2) % 3];
+        a.pold2 = v.p[(k + 1) % 3];
+        a.pnew = v.p[k % 3];
+        a.qold = v.q[(k + 1) & 1];
+        a.q = v.q[k & 1];
+        a.x = v.x;
+        a.part_in = k == 0 ? ctx->part(PS_U) : ctx->part(PS_CG + kCgCols * ((k + 1) & 1));
+        a.nb_in = k == 0 ? nb_first : nb_cg;
+        a.part_out = ctx->part(PS_CG + kCgCols * (k & 1));
+        a.fresh = fresh ? 1 : 0;
+        a.maxit = maxit;
+        a.xzero = xzero ? 1 : 0;
+        O::pcg_iter(ctx->L, ctx->TS, ctx->stream, ctx->ph, ctx->st, k, a);
     };
-    iter(0);
+    // launches k0..k1-1, back to back; when profiling, bracketed as one run
+    // (per-launch events would add their own packets between the launches)
+    auto run = [&](int k0, int k1) {
+        Prof& pf = ctx->prof;
+        const size_t ea = pf.on ? pf.take() : (size_t)-1;
+        const size_t eb = pf.on ? pf.take() : (size_t)-1;
+        const bool bracket = ea != (size_t)-1 && eb != (size_t)-1;
+        if (bracket) (void)hipEventRecord(pf.pool[ea], ctx->stream);
+        for (int k = k0; k < k1; ++k) launch(k);
+        if (!bracket) return;
+        (void)hipEventRecord(pf.pool[eb], ctx->stream);
+        // words of an iteration: r, diag, w read, p, q written; from k = 1 also
+        // q, p_old read and r written; at even k >= 2 also p_{k-2} read and x
+        // updated.  Stopping at k >= 1: x += alpha p_old (odd k) or the two
+        // pending updates (even k), x not read while it has not been written
+        // (zero start, k <= 2).
+        const double cell = (double)ctx->es * (double)ctx->NT();
+        for (int k = k0; k < k1; ++k) {
+            const double words = k == 0 ? 5.0 : (k & 1) ? 8.0 : 11.0;
+            const double xread = xzero && k <= 2 ? 0.0 : 1.0;
+            const double stop = k == 0 ? 0.0 : ((k & 1) ? 2.0 : 3.0) + xread;
+            pf.pending.push_back({KC_PCG_SPMV, ea, eb, words * cell, k, stop * cell});
+        }
+    };
     int k = 0;  // iterations launched: 0..k
     if (!eager) {
         const int cap = std::min(std::max(1, iters), maxit);
-        for (; k < cap; ++k) iter(k + 1);
+        run(0, cap + 1);
         return PISOC_OK;
     }
     int batch = std::max(1, iters);
     int most = 0;
-    for (;;) {
+    for (bool first = true;; first = false) {
         const int kend = std::min(k + batch, maxit);
-        for (; k < kend; ++k) iter(k + 1);
+        run(first ? 0 : k + 1, kend + 1);
+        k = std::max(k, kend);
         pisoc_status s = sync_state(ctx);
         if (s != PISOC_OK) return s;
         bool all = true, bad_dt = false;
@@ -996,7 +1042,8 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     if (prm->guess == PISOC_GUESS_LEARNED && prm->guess_audit > 0) {
         bool ok = true;
         for (auto& row : ctx->audit.ev)
-            for (auto& e : row) ok = ok && hipEventCreate(&e) == hipSuccess;
+            for (auto& e : row)   // timing only, as the profiler's
+                ok = ok && hipEventCreateWithFlags(&e, hipEventDisableSystemFence) == hipSuccess;
         ctx->audit.have_events = ok;
         if (!ok) {
             ctx->err = "hipEventCreate failed";
