@@ -1308,6 +1308,8 @@ bool cache_store(const char* path, const std::string& key, int bx, int cz) {
     return true;
 }
 
+// CG iterations in a launch-shape probe
+constexpr int kProbeCgIters = 12;
 template <typename T>
 void enqueue_probe(pisoc_ctx* ctx) {
     using O = Ops<T>;
@@ -1320,9 +1322,11 @@ void enqueue_probe(pisoc_ctx* ctx) {
     O::hbya(L, ctx->TL, s, ph, st, S.ua, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0);
     const unsigned nb0 = O::corr_rhs(L, ctx->TL, s, ph, st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH,
                                      S.r, S.dg, ctx->part(PS_U), nullptr, nullptr, nullptr, S.b64);
-    // two CG iterations that cannot converge (tolerance 0)
+    // CG iterations that cannot converge (tolerance 0), about as many against
+    // the field kernels as in a step (two solves of 10-20 iterations each
+    // against 6-8 momentum sweeps)
     set_tol(s, st, ctx->batch, 0.0);
-    (void)run_pcg<T>(ctx, cg_vecs(S), true, 1, false, nullptr, true, nb0);
+    (void)run_pcg<T>(ctx, cg_vecs(S), true, kProbeCgIters, false, nullptr, true, nb0);
     if (ctx->prm.n_classes > 0) O::dust_sweep(L, ctx->TL, s, ph, st, S.Ya, S.Yb, S.G, S.rj, S.rk);
 }
 
@@ -1433,29 +1437,35 @@ pisoc_status build_graphs(pisoc_ens* e) {
     e->exec.assign(e->cls.size(), {nullptr, nullptr});
     for (pisoc_ctx* ctx : e->cls)
         if (audit_on(ctx)) audit_decide_capture(ctx);
+    // on failure: no graph kept, the buffers' rotation as before the call
+    auto fail = [&](int par, pisoc_status st, const std::string& why) {
+        e->err = why;
+        if (par == 1)
+            for (pisoc_ctx* ctx : e->cls) rotate(ctx);
+        drop_graphs(e);
+        return st;
+    };
     for (int par = 0; par < 2; ++par) {
         for (size_t c = 0; c < e->cls.size(); ++c) {
             pisoc_ctx* ctx = e->cls[c];
             hipGraph_t g = nullptr;
-            if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-                e->err = "hipStreamBeginCapture failed";
-                return PISOC_ERR_HIP;
-            }
+            if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return fail(par, PISOC_ERR_HIP, "hipStreamBeginCapture failed");
             const pisoc_status st = ctx->prm.precision == PISOC_FP64 ? enqueue_step<double>(ctx, false)
                                                                      : enqueue_step<float>(ctx, false);
             const hipError_t rc_end = hipStreamEndCapture(ctx->stream, &g);
             if (st != PISOC_OK || rc_end != hipSuccess || !g) {
                 if (g) (void)hipGraphDestroy(g);
-                e->err = std::string("graph capture failed: ") +
-                         (st != PISOC_OK ? ctx->err : std::string(hipGetErrorString(rc_end)));
-                return st != PISOC_OK ? st : PISOC_ERR_HIP;
+                return fail(par, st != PISOC_OK ? st : PISOC_ERR_HIP,
+                            std::string("graph capture failed: ") +
+                                (st != PISOC_OK ? ctx->err : std::string(hipGetErrorString(rc_end))));
             }
             const hipError_t rc = hipGraphInstantiate(&e->exec[c][par], g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (rc != hipSuccess) {
                 e->exec[c][par] = nullptr;
-                e->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(rc);
-                return PISOC_ERR_HIP;
+                return fail(par, PISOC_ERR_HIP,
+                            std::string("hipGraphInstantiate: ") + hipGetErrorString(rc));
             }
         }
         for (pisoc_ctx* ctx : e->cls) rotate(ctx);
