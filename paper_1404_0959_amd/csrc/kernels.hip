@@ -1019,13 +1019,14 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(
     block_partials<CG_COLS, 0u>(v, part_out);
 }
 
-// Tiled form for n a multiple of 64: a block owns a 64 x 8 column tile and
+// Tiled form: a block of TX x NTY threads owns a TX x (NTY RPT) column tile
+// (64 x 8 for n a multiple of 64, 16 x 16 for the other multiples of 16) and
 // marches along z.  Each of r, q, p_old, diag and w is read once per cell
 // from HBM: the x-y neighbours of the current plane come from LDS tiles (halo
 // 2 for w; halo 1 for the direction p, formed from r, q, p_old and diag at
 // the halo cells), the z neighbours from per-thread register queues.
-template <typename T, int RPT, int XM>
-__global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
+template <typename T, int RPT, int XM, int TX, int NTY>
+__global__ void __launch_bounds__(TX * NTY) k_pcg_spmv_tiled(
     Phys ph, DevState* st, int k, const T* __restrict__ rin, T* __restrict__ rout,
     const T* __restrict__ diag, const T* __restrict__ w, const T* __restrict__ pold,
     const T* __restrict__ pold2, T* __restrict__ pnew, const T* __restrict__ qold,
@@ -1039,9 +1040,9 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     const T alpha = (T)h.alpha, beta = (T)h.beta;
     const T inv_h2 = (T)ph.inv_h2;
     const int n = ph.n, cz = ph.cz;
-    constexpr int TY = kTY * RPT;               // tile rows; thread row ty owns rows ty + e kTY
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kTX * ty;
-    const int i0 = bp_.x * kTX, j0 = bp_.y * TY;
+    constexpr int TY = NTY * RPT;               // tile rows; thread row ty owns rows ty + e NTY
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
+    const int i0 = bp_.x * TX, j0 = bp_.y * TY;
     const int k0 = bz_ * cz;
     const int k1 = k0 + cz < n ? k0 + cz : n;
     const size_t nn = (size_t)n * n;
@@ -1050,7 +1051,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
         if ((UPD || xzero) && !h.skip) {
 #pragma unroll
             for (int e = 0; e < RPT; ++e) {
-                const size_t c0 = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty + e * kTY);
+                const size_t c0 = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty + e * NTY);
                 for (int kk = k0; kk < k1; ++kk) {
                     const size_t Q = c0 + nn * (size_t)kk;
                     x[Q] = XE    ? xu.two(x[Q], pold2[Q], pold[Q])
@@ -1061,8 +1062,8 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
         }
         return;
     }
-    __shared__ T ws[TY + 4][kTX + 4];
-    __shared__ T ps[TY + 2][kTX + 2];
+    __shared__ T ws[TY + 4][TX + 4];
+    __shared__ T ps[TY + 2][TX + 2];
     auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
     // r_k and p_k of a cell from its r_{k-1}, q_{k-1}, diag, p_{k-1}
     auto resf = [&](T ro, T qo) -> T { return UPD ? ro - alpha * qo : ro; };
@@ -1076,7 +1077,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
     T oc[RPT], xc[RPT], xn1[RPT], o2c[RPT], o2n1[RPT];
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
-        col[e] = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty + e * kTY);
+        col[e] = base_ + (size_t)(i0 + tx) + (size_t)n * (j0 + ty + e * NTY);
         wq0[e] = w[col[e] + nn * wr(k0 - 2)];
         wq1[e] = w[col[e] + nn * wr(k0 - 1)];
         wq2[e] = w[col[e] + nn * k0];
@@ -1095,33 +1096,33 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
         }
     }
     // this thread's halo cell, if any (same x-y position on every plane):
-    // w rows j0-2, j0-1, j0+TY, j0+TY+1; w columns i0-2, i0-1, i0+64, i0+65;
-    // p rows j0-1, j0+TY; p columns i0-1, i0+64
-    constexpr int nWR = 4 * kTX, nWC = 4 * TY, nPR = 2 * kTX, nPC = 2 * TY;
-    static_assert(nWR + nWC + nPR + nPC <= kTX * kTY, "one halo cell per thread");
+    // w rows j0-2, j0-1, j0+TY, j0+TY+1; w columns i0-2, i0-1, i0+TX, i0+TX+1;
+    // p rows j0-1, j0+TY; p columns i0-1, i0+TX
+    constexpr int nWR = 4 * TX, nWC = 4 * TY, nPR = 2 * TX, nPC = 2 * TY;
+    static_assert(nWR + nWC + nPR + nPC <= TX * NTY, "one halo cell per thread");
     int hkind = 0, hy = 0, hx = 0;
     size_t hoff = 0;
     if (tid < nWR) {
-        const int row = tid / kTX, xx = tid - row * kTX;
+        const int row = tid / TX, xx = tid - row * TX;
         hy = row < 2 ? row : TY + row;
         hx = xx + 2;
         hoff = base_ + (size_t)(i0 + xx) + (size_t)n * wr(j0 - 2 + hy);
         hkind = 1;
     } else if (tid < nWR + nWC) {
         const int t2 = tid - nWR, c4 = t2 / TY, y = t2 - c4 * TY;
-        hx = c4 < 2 ? c4 : kTX + c4;
+        hx = c4 < 2 ? c4 : TX + c4;
         hy = y + 2;
         hoff = base_ + (size_t)wr(i0 - 2 + hx) + (size_t)n * (j0 + y);
         hkind = 1;
     } else if (tid < nWR + nWC + nPR) {
-        const int t3 = tid - nWR - nWC, row = t3 / kTX, xx = t3 - row * kTX;
+        const int t3 = tid - nWR - nWC, row = t3 / TX, xx = t3 - row * TX;
         hy = row == 0 ? 0 : TY + 1;
         hx = xx + 1;
         hoff = base_ + (size_t)(i0 + xx) + (size_t)n * wr(j0 - 1 + hy);
         hkind = 2;
     } else if (tid < nWR + nWC + nPR + nPC) {
         const int t4 = tid - nWR - nWC - nPR, c2 = t4 / TY, y = t4 - c2 * TY;
-        hx = c2 == 0 ? 0 : kTX + 1;
+        hx = c2 == 0 ? 0 : TX + 1;
         hy = y + 1;
         hoff = base_ + (size_t)wr(i0 - 1 + hx) + (size_t)n * (j0 + y);
         hkind = 2;
@@ -1196,15 +1197,15 @@ __global__ void __launch_bounds__(kTX * kTY) k_pcg_spmv_tiled(
         }
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
-            ws[ty + e * kTY + 2][tx + 2] = wq2[e];
-            ps[ty + e * kTY + 1][tx + 1] = pc[e];
+            ws[ty + e * NTY + 2][tx + 2] = wq2[e];
+            ps[ty + e * NTY + 1][tx + 1] = pc[e];
         }
         if (hkind == 1) ws[hy][hx] = hwc;
         else if (hkind == 2) ps[hy][hx] = hpc;
         lds_barrier();
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
-            const int y = ty + e * kTY;
+            const int y = ty + e * NTY;
             const T kxp = (T(9) * (ws[y + 2][tx + 2] + ws[y + 2][tx + 3]) -
                            (ws[y + 2][tx + 1] + ws[y + 2][tx + 4])) * T(0.0625);
             const T kxm = (T(9) * (ws[y + 2][tx + 1] + ws[y + 2][tx + 2]) -
@@ -2812,14 +2813,17 @@ Launch make_spmv_launch(int n, int batch, int elem_bytes) {
         return L;
     }
     constexpr int TY = kTY * kSpmvRows;
-    if (n < 64 || n % kTX != 0 || n % TY != 0) return L;   // nblocks = 0: not available
-    const int gx = n / kTX, gy = n / TY;
+    const bool wide = n >= 64 && n % kTX == 0 && n % TY == 0;
+    if (!wide && n % kSmallTX != 0) return L;   // nblocks = 0: not available
+    const int tx = wide ? kTX : kSmallTX, ty = wide ? TY : kSmallTX;
+    const int gx = n / tx, gy = n / ty;
     int nz = kTiledBlocks / (gx * gy);
     nz = nz < 1 ? 1 : nz;
     int cz = (n + nz - 1) / nz;
-    if (cz < 8) cz = 8;
+    const int cz_min = wide ? 8 : 4;
+    if (cz < cz_min) cz = cz_min;
     nz = (n + cz - 1) / cz;
-    L.block = dim3(kTX, kTY, 1);
+    L.block = wide ? dim3(kTX, kTY, 1) : dim3(kSmallTX, kSmallTX, 1);
     L.grid = dim3(gx, gy, nz * batch);
     L.nblocks = L.grid.x * L.grid.y * L.grid.z;
     L.cz = cz;
@@ -2991,7 +2995,10 @@ static void spmv_launch(const Launch& L, const Launch& TL, hipStream_t s, const 
         Phys pt = ph;
         pt.cz = TL.cz;
         pt.nz = TL.nz;
-        LAUNCH((k_pcg_spmv_tiled<T, kSpmvRows, XM>), TL, s, pt, SPMV_ARGS);
+        if (TL.block.x == kSmallTX)
+            LAUNCH((k_pcg_spmv_tiled<T, 1, XM, kSmallTX, kSmallTX>), TL, s, pt, SPMV_ARGS);
+        else
+            LAUNCH((k_pcg_spmv_tiled<T, kSpmvRows, XM, kTX, kTY>), TL, s, pt, SPMV_ARGS);
     } else {
         LAUNCH((k_pcg_spmv<T, XM>), L, s, ph, SPMV_ARGS);
     }

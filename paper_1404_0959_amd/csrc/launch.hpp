@@ -40,9 +40,12 @@ Launch make_tiled_launch(int n, int batch = 1);
 // n = 64 kRowCells and FP32: the full-row form, blocks of kRowWaves
 // wavefronts each owning one x-row (kRowCells cells per lane), about
 // kRowBlocks blocks per member (v = kRowCells; in FP64 its registers would
-// not fit).  Otherwise tiles of 64 x (8 kSpmvRows) cells, 64 x 8 threads each
-// owning kSpmvRows rows (v = 0); nblocks is 0 when neither is available.
+// not fit).  Otherwise, for n a multiple of 64, tiles of 64 x (8 kSpmvRows)
+// cells, 64 x 8 threads each owning kSpmvRows rows (v = 0); for the other
+// multiples of kSmallTX, tiles of kSmallTX x kSmallTX cells, one thread per
+// column (block.x = kSmallTX); nblocks is 0 when none is available.
 constexpr int kSpmvRows = 1;
+constexpr int kSmallTX = 16;
 constexpr int kRowCells = 4, kRowWaves = 8, kRowBlocks = 256;
 Launch make_spmv_launch(int n, int batch, int elem_bytes);
 

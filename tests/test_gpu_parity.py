@@ -171,11 +171,12 @@ def test_step_parity_hit128_tiled(P, ora, n):
     compare_state(P, ora, s, o)
 
 
-@pytest.mark.parametrize("n", [64, 128])
+@pytest.mark.parametrize("n", [32, 48, 64, 128])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_tiled_kernels_match_gathered(P, monkeypatch, precision, n):
     """At n = 64 and 128 the stencil kernels run as tiled z-marches (the generic k_tiled
-    driver, the tiled corrector set-up, momentum sweep and CG kernel); with
+    driver, the tiled corrector set-up, momentum sweep and CG kernel); at 32 and
+    48 only the CG kernel does, on 16 x 16 tiles; with
     PISOC_UNTILED=1 the same step runs the gathered kernels. Both call the same
     cell arithmetic; only reduction order differs, so the CG iteration counts
     agree and the fields agree to rounding (FP64: 1e-11 of the spread; FP32:
