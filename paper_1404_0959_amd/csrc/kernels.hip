@@ -2820,8 +2820,7 @@ Launch make_spmv_launch(int n, int batch, int elem_bytes) {
     int nz = kTiledBlocks / (gx * gy);
     nz = nz < 1 ? 1 : nz;
     int cz = (n + nz - 1) / nz;
-    const int cz_min = wide ? 8 : 4;
-    if (cz < cz_min) cz = cz_min;
+    if (cz < 8) cz = 8;   // 4 or 2 planes: slower at 32^3-48^3 (z halo, launch of more blocks)
     nz = (n + cz - 1) / cz;
     L.block = wide ? dim3(kTX, kTY, 1) : dim3(kSmallTX, kSmallTX, 1);
     L.grid = dim3(gx, gy, nz * batch);

@@ -43,7 +43,8 @@ Launch make_tiled_launch(int n, int batch = 1);
 // not fit).  Otherwise, for n a multiple of 64, tiles of 64 x (8 kSpmvRows)
 // cells, 64 x 8 threads each owning kSpmvRows rows (v = 0); for the other
 // multiples of kSmallTX, tiles of kSmallTX x kSmallTX cells, one thread per
-// column (block.x = kSmallTX); nblocks is 0 when none is available.
+// column (block.x = kSmallTX); nblocks is 0 when none is available.  Tiles
+// march over at least 8 planes.
 constexpr int kSpmvRows = 1;
 constexpr int kSmallTX = 16;
 constexpr int kRowCells = 4, kRowWaves = 8, kRowBlocks = 256;
