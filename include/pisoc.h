@@ -236,6 +236,8 @@ typedef struct {
     int32_t rounds;                     /* ... FP64 refinement rounds (FP32_REFINED) */
     int32_t guess_mask;                 /* ... bit c set: corrector c's solve starts from
                                            the learned guess */
+    int32_t cg_cells_z;                 /* planes per block of the CG kernel's z-march
+                                           (0: its gathered form) */
 } pisoc_ens_class;
 
 /* Workspace for the ensemble (0 if the members are invalid); 256-byte aligned. */
@@ -270,12 +272,15 @@ pisoc_status pisoc_ens_class_info(const pisoc_ens* ens, int32_t cls, pisoc_ens_c
 /* Launch-shape autotuner: for every size class, times each candidate shape of
  * the field kernels (block bx x 256/bx threads, cz cells per thread along z,
  * at most 4096 blocks per member) on a representative set of the step's
- * kernels -- a predictor sweep, H/A, the corrector set-up, two CG iterations
- * and a dust sweep -- run on the systems of the last step, and keeps the
- * fastest.  Winners are cached in the JSON file cache_path (may be NULL) under
- * a key of grid size, members, precision, dust classes and guess; a cached
- * entry is used without timing unless force != 0.  Needs one completed step.
- * Synchronises; the captured graph is rebuilt on the next call. */
+ * kernels -- a predictor sweep, H/A, the corrector set-up, twelve CG
+ * iterations and a dust sweep -- run on the systems of the last step, and
+ * keeps the fastest; then, with that shape and where the CG kernel runs on
+ * tiles, the planes per block of its z-march (its default, 8, 16 or 32).
+ * Winners are cached in the JSON file cache_path (may be NULL) as [bx, cz, CG
+ * planes (0: none)] under a key of grid size, members, precision, dust
+ * classes and guess; a cached entry is used without timing unless force != 0.
+ * Needs one completed step.  Synchronises; the captured graph is rebuilt on
+ * the next call. */
 pisoc_status pisoc_ens_autotune(pisoc_ens* ens, const char* cache_path, int32_t force);
 
 void pisoc_ens_destroy(pisoc_ens* ens);

@@ -2796,7 +2796,7 @@ Launch make_tiled_launch(int n, int batch) {
     return L;
 }
 
-Launch make_spmv_launch(int n, int batch, int elem_bytes) {
+Launch make_spmv_launch(int n, int batch, int elem_bytes, int cz_tile) {
     Launch L{};
     if (n == 64 * kRowCells && elem_bytes == 4) {   // full-row form
         const int gy = n / kRowWaves;
@@ -2821,6 +2821,7 @@ Launch make_spmv_launch(int n, int batch, int elem_bytes) {
     nz = nz < 1 ? 1 : nz;
     int cz = (n + nz - 1) / nz;
     if (cz < 8) cz = 8;   // 4 or 2 planes: slower at 32^3-48^3 (z halo, launch of more blocks)
+    if (cz_tile > 0) cz = cz_tile < n ? cz_tile : n;
     nz = (n + cz - 1) / cz;
     L.block = wide ? dim3(kTX, kTY, 1) : dim3(kSmallTX, kSmallTX, 1);
     L.grid = dim3(gx, gy, nz * batch);

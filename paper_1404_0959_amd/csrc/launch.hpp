@@ -44,11 +44,12 @@ Launch make_tiled_launch(int n, int batch = 1);
 // cells, 64 x 8 threads each owning kSpmvRows rows (v = 0); for the other
 // multiples of kSmallTX, tiles of kSmallTX x kSmallTX cells, one thread per
 // column (block.x = kSmallTX); nblocks is 0 when none is available.  Tiles
-// march over at least 8 planes.
+// march over at least 8 planes, or exactly min(cz_tile, n) when cz_tile > 0
+// (a tuned choice; the full-row form ignores it).
 constexpr int kSpmvRows = 1;
 constexpr int kSmallTX = 16;
 constexpr int kRowCells = 4, kRowWaves = 8, kRowBlocks = 256;
-Launch make_spmv_launch(int n, int batch, int elem_bytes);
+Launch make_spmv_launch(int n, int batch, int elem_bytes, int cz_tile = 0);
 
 // Partial-sum columns written by one CG iteration.
 constexpr int kCgCols = 7;

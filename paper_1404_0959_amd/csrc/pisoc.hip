@@ -181,6 +181,8 @@ Layout make_layout(const pisoc_params* p, int batch) {
     const size_t es = p->precision == PISOC_FP64 ? sizeof(double) : sizeof(float);
     unsigned mb = std::max({make_launch(p->n, batch).nblocks, make_tiled_launch(p->n, batch).nblocks,
                             make_spmv_launch(p->n, batch, (int)es).nblocks});
+    for (int c : {8, 16, 32})   // the CG chunks the autotuner may choose
+        mb = std::max(mb, make_spmv_launch(p->n, batch, (int)es, c).nblocks);
     for (auto [bx, cz] : shape_candidates(p->n))
         mb = std::max(mb, make_launch_shaped(p->n, batch, bx, cz).nblocks);
     L.max_blocks = mb;
@@ -1258,14 +1260,16 @@ std::string tune_key(const pisoc_ctx* ctx) {
     return b;
 }
 
-bool cache_lookup(const std::string& text, const std::string& key, int* bx, int* cz) {
+// An entry is [block x, cells per thread along z, CG tile planes (0: the CG
+// kernel has no tile form at this size)].
+bool cache_lookup(const std::string& text, const std::string& key, int* bx, int* cz, int* cgz) {
     const std::string pat = "\"" + key + "\"";
     size_t at = text.find(pat);
     if (at == std::string::npos) return false;
     at = text.find('[', at + pat.size());
     if (at == std::string::npos) return false;
-    return std::sscanf(text.c_str() + at, "[%d , %d]", bx, cz) == 2 ||
-           std::sscanf(text.c_str() + at, "[%d,%d]", bx, cz) == 2;
+    return std::sscanf(text.c_str() + at, "[%d , %d , %d]", bx, cz, cgz) == 3 ||
+           std::sscanf(text.c_str() + at, "[%d,%d,%d]", bx, cz, cgz) == 3;
 }
 
 std::string read_file(const char* path) {
@@ -1281,9 +1285,9 @@ std::string read_file(const char* path) {
 }
 
 // Rewrite the cache with the entry for key replaced or added.
-bool cache_store(const char* path, const std::string& key, int bx, int cz) {
+bool cache_store(const char* path, const std::string& key, int bx, int cz, int cgz) {
     std::string text = read_file(path);
-    std::vector<std::pair<std::string, std::pair<int, int>>> entries;
+    std::vector<std::pair<std::string, std::array<int, 3>>> entries;
     size_t pos = 0;
     for (;;) {
         const size_t q0 = text.find('"', pos);
@@ -1291,18 +1295,18 @@ bool cache_store(const char* path, const std::string& key, int bx, int cz) {
         const size_t q1 = text.find('"', q0 + 1);
         if (q1 == std::string::npos) break;
         const std::string k = text.substr(q0 + 1, q1 - q0 - 1);
-        int a, b;
-        if (cache_lookup(text.substr(q0), k, &a, &b) && k != key) entries.push_back({k, {a, b}});
+        int a, b, c;
+        if (cache_lookup(text.substr(q0), k, &a, &b, &c) && k != key) entries.push_back({k, {a, b, c}});
         pos = text.find(']', q1);
         if (pos == std::string::npos) break;
     }
-    entries.push_back({key, {bx, cz}});
+    entries.push_back({key, {bx, cz, cgz}});
     FILE* f = std::fopen(path, "wb");
     if (!f) return false;
     std::fprintf(f, "{\n");
     for (size_t i = 0; i < entries.size(); ++i)
-        std::fprintf(f, "  \"%s\": [%d, %d]%s\n", entries[i].first.c_str(), entries[i].second.first,
-                     entries[i].second.second, i + 1 < entries.size() ? "," : "");
+        std::fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", entries[i].first.c_str(), entries[i].second[0],
+                     entries[i].second[1], entries[i].second[2], i + 1 < entries.size() ? "," : "");
     std::fprintf(f, "}\n");
     std::fclose(f);
     return true;
@@ -1330,14 +1334,38 @@ void enqueue_probe(pisoc_ctx* ctx) {
     if (ctx->prm.n_classes > 0) O::dust_sweep(L, ctx->TL, s, ph, st, S.Ya, S.Yb, S.G, S.rj, S.rk);
 }
 
+// The CG kernel's tile launch with z-chunks of cgz planes (0: the default).
+void set_cg_chunk(pisoc_ctx* ctx, int cgz) {
+    ctx->TS = make_spmv_launch(ctx->prm.n, ctx->batch, (int)ctx->es, cgz);
+}
+
+// Only the tile form of the CG kernel takes a tuned z-chunk.
+bool cg_tunable(const pisoc_ctx* ctx) { return ctx->TS.nblocks && ctx->TS.v == 0; }
+
+// The default chunk, then 8, 16 and 32 planes (at most n), each once.
+std::vector<int> cg_chunk_candidates(const pisoc_ctx* ctx) {
+    std::vector<int> out{make_spmv_launch(ctx->prm.n, ctx->batch, (int)ctx->es).cz};
+    for (int c : {8, 16, 32})
+        if (c <= ctx->prm.n && std::find(out.begin(), out.end(), c) == out.end()) out.push_back(c);
+    return out;
+}
+
+// Launch shapes of one size class: the gathered kernels' block and cells per
+// thread (timed over the shape candidates), then, with that shape, the CG
+// kernel's tile z-chunk (timed over cg_chunk_candidates), each by the probe
+// step; or the cached choice.
 pisoc_status tune_ctx(pisoc_ctx* ctx, const char* cache_path, int force, int* bx_out, int* cz_out) {
     const std::string key = tune_key(ctx);
-    int bx = 0, cz = 0;
-    if (!force && cache_lookup(read_file(cache_path), key, &bx, &cz)) {
-        bool ok = false;
+    const bool cgt = cg_tunable(ctx);
+    int bx = 0, cz = 0, cgz = 0;
+    if (!force && cache_lookup(read_file(cache_path), key, &bx, &cz, &cgz)) {
+        bool ok = false, okc = !cgt && cgz == 0;
         for (auto [a, b] : shape_candidates(ctx->prm.n)) ok = ok || (a == bx && b == cz);
-        if (ok) {
+        if (cgt)
+            for (int c : cg_chunk_candidates(ctx)) okc = okc || c == cgz;
+        if (ok && okc) {
             set_shape(ctx, make_launch_shaped(ctx->prm.n, ctx->batch, bx, cz));
+            if (cgt) set_cg_chunk(ctx, cgz);
             *bx_out = bx;
             *cz_out = cz;
             return PISOC_OK;
@@ -1348,39 +1376,58 @@ pisoc_status tune_ctx(pisoc_ctx* ctx, const char* cache_path, int force, int* bx
     HIP_TRY(ctx, hipEventCreate(&e1));
     const bool prof = ctx->prof.on;
     ctx->prof.on = false;
-    float best = 1e30f;
-    int best_bx = 0, best_cz = 0;
-    const Launch L0 = ctx->L;
-    for (auto [a, b] : shape_candidates(ctx->prm.n)) {
-        set_shape(ctx, make_launch_shaped(ctx->prm.n, ctx->batch, a, b));
-        auto probe = [&] {
-            if (ctx->prm.precision == PISOC_FP64) enqueue_probe<double>(ctx);
-            else enqueue_probe<float>(ctx);
-        };
-        probe();  // warm-up
+    auto probe = [&] {
+        if (ctx->prm.precision == PISOC_FP64) enqueue_probe<double>(ctx);
+        else enqueue_probe<float>(ctx);
+    };
+    // time of three probe steps after a warm-up one, or a negative value
+    auto time_probe = [&]() -> float {
+        probe();
         (void)hipEventRecord(e0, ctx->stream);
         for (int rep = 0; rep < 3; ++rep) probe();
         (void)hipEventRecord(e1, ctx->stream);
-        if (hipEventSynchronize(e1) != hipSuccess) break;
+        if (hipEventSynchronize(e1) != hipSuccess) return -1.f;
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
+        return hipEventElapsedTime(&ms, e0, e1) == hipSuccess ? ms : -1.f;
+    };
+    float best = 1e30f;
+    int best_bx = 0, best_cz = 0, best_cgz = 0;
+    const Launch L0 = ctx->L;
+    for (auto [a, b] : shape_candidates(ctx->prm.n)) {
+        set_shape(ctx, make_launch_shaped(ctx->prm.n, ctx->batch, a, b));
+        const float ms = time_probe();
+        if (ms < 0.f) break;
         if (ms < best) {
             best = ms;
             best_bx = a;
             best_cz = b;
         }
     }
+    if (best_bx != 0) set_shape(ctx, make_launch_shaped(ctx->prm.n, ctx->batch, best_bx, best_cz));
+    if (best_bx != 0 && cgt) {
+        float best_c = 1e30f;
+        for (int c : cg_chunk_candidates(ctx)) {
+            set_cg_chunk(ctx, c);
+            const float ms = time_probe();
+            if (ms < 0.f) break;
+            if (ms < best_c) {
+                best_c = ms;
+                best_cgz = c;
+            }
+        }
+        set_cg_chunk(ctx, best_cgz);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->prof.on = prof;
     HIP_TRY(ctx, hipGetLastError());
-    if (best_bx == 0) {
+    if (best_bx == 0 || (cgt && best_cgz == 0)) {
         set_shape(ctx, L0);
+        if (cgt) set_cg_chunk(ctx, 0);
         ctx->err = "no launch shape could be timed";
         return PISOC_ERR_HIP;
     }
-    set_shape(ctx, make_launch_shaped(ctx->prm.n, ctx->batch, best_bx, best_cz));
-    if (cache_path && !cache_store(cache_path, key, best_bx, best_cz)) {
+    if (cache_path && !cache_store(cache_path, key, best_bx, best_cz, best_cgz)) {
         ctx->err = std::string("cannot write ") + cache_path;
         return PISOC_ERR_INVALID;
     }
@@ -1884,6 +1931,7 @@ pisoc_status pisoc_ens_class_info(const pisoc_ens* e, int32_t cls, pisoc_ens_cla
     for (int c = 0; c < ctx->prm.n_corr; ++c)
         if (ctx->prm.guess == PISOC_GUESS_LEARNED && (!audit_on(ctx) || ctx->audit.use[c]))
             o.guess_mask |= 1 << c;
+    o.cg_cells_z = ctx->TS.nblocks ? ctx->TS.cz : 0;
     *h_out = o;
     return PISOC_OK;
 }
