@@ -754,8 +754,17 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
             if (done) break;
         }
         if (sol_in_x) {
-            // x64 = d before the next round's solve overwrites d
+            // x64 = d before the next round's solve overwrites d, and the
+            // FP32 copy xf = d: a member already converged skips the later
+            // rounds' refinement, which would otherwise have written xf, and
+            // the corrector takes its solution from xf
             Ops<float>::cast_out(s, S.x, xa, ctx->NT(), 0.0);
+            if (hipMemcpyAsync(S.xf, S.x, sizeof(float) * ctx->NT(), hipMemcpyDeviceToDevice, s) !=
+                hipSuccess) {
+                ctx->err = "hipMemcpyAsync failed";
+                *err = PISOC_ERR_HIP;
+                return;
+            }
             sol_in_x = false;
         }
         set_tol_refine(s, ctx->st, B, p.inner_tol);

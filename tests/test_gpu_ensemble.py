@@ -190,6 +190,52 @@ def test_graph_keeps_audit_verdict(P):
         assert np.max(np.abs(ua - ub)) <= 1e-4 * np.max(np.abs(ua)), m
 
 
+def test_bench_ensemble_configuration(P, tmp_path):
+    """The ensemble the benchmark times, at its full size: 64 members (32 x
+    32^3, 16 x 48^3, 16 x 64^3), FP32 + learned guess under the audit,
+    autotuned, captured steps.  Every solve meets the tolerance, gas and dust
+    mass are conserved, and the first member of each size class agrees with
+    the same case stepped alone to 1e-5 of max |u| (in practice bitwise: a
+    member's reductions do not depend on the other members).  Regression: a
+    member converged in an eager step's first FP32 round, in a class where
+    another member needed a second round, once took a stale solution copy."""
+    from paper_1404_0959_amd.learn import load_weights
+    w = load_weights()
+    cs = ensemble_cases(64, seed=0)
+    assert [sum(1 for c in cs if c.n == n) for n in (32, 48, 64)] == [32, 16, 16]
+    kw = dict(p_tol=1e-6, cfl=0.5, n_corr=2, n_mom_sweeps=4, n_dust_sweeps=4,
+              precision=P.FP32_REFINED, inner_tol=1e-6, guess=P.GUESS_LEARNED,
+              guess_weights=w.data_ptr(), guess_audit=16)
+    E = P.Ensemble(cs, **kw)
+    m0 = [s["mass_gas"] for s in E.stats()]
+    p0 = [s["mass_p"][0] for s in E.stats()]
+    st, info = E.step(1, mode=P.ENS_EAGER)
+    assert st in (P.OK, P.WARN_GUESS_FALLBACK)
+    E.autotune(str(tmp_path / "tune.json"), force=True)
+    for c in E.classes():
+        assert c["cg_cells_z"] > 0      # every class runs the tiled CG kernel
+    st, info = E.step(6, mode=P.ENS_GRAPH)
+    assert st in (P.OK, P.WARN_GUESS_FALLBACK), st
+    assert E.steps_done == 7
+    stats = E.stats()
+    for m in range(len(cs)):
+        assert max(info[m]["pcg_relres"]) <= 1e-6, (m, info[m])
+        assert not info[m]["flags"] & P.FLAG_PCG_MAXIT
+        assert abs(stats[m]["mass_gas"] - m0[m]) <= 1e-10 * m0[m]
+        assert abs(stats[m]["mass_p"][0] - p0[m]) <= 1e-7 * p0[m]
+    firsts = [min(m for m, c in enumerate(cs) if c.n == n) for n in (32, 48, 64)]
+    for m in firsts:
+        s = P.Solver.from_case(cs[m], **kw)
+        st1, _ = s.step(7)
+        assert st1 in (P.OK, P.WARN_GUESS_FALLBACK)
+        assert abs(s.t - E.times()[m]) <= 1e-4 * s.t
+        ua = s.get(P.FIELD_U).cpu().numpy()
+        ub = E.get(m, P.FIELD_U).cpu().numpy()
+        assert np.max(np.abs(ua - ub)) <= 1e-5 * np.max(np.abs(ua)), m
+        s.close()
+    E.close()
+
+
 def test_autotune_cache_round_trip(P, tmp_path):
     cs = cases()
     kw = dict(p_tol=1e-8)
