@@ -1257,10 +1257,11 @@ pisoc_status all_stats(pisoc_ctx* ctx, pisoc_stats* out) {
 // ---------------------------------------------------------------- autotuner
 // Launch shapes of the field kernels are tuned per (n, members, precision,
 // dust classes): each candidate (bx, cz) times a representative set of field
-// kernels -- a predictor sweep, H/A, the corrector set-up, two CG iterations
-// and a dust sweep -- on the context's own buffers (all of them scratch
-// between steps; the persistent state is only read), and the fastest wins.
-// Winners are kept in a small JSON object {"key": [bx, cz], ...}.
+// kernels -- a predictor sweep, H/A, the corrector set-up, kProbeCgIters CG
+// iterations and a dust sweep -- on the context's own buffers (all of them
+// scratch between steps; the persistent state is only read), and the fastest
+// wins; the CG kernel's tile z-chunk is then chosen the same way.  Winners
+// are kept in a small JSON object {"key": [bx, cz, CG planes], ...}.
 std::string tune_key(const pisoc_ctx* ctx) {
     char b[96];
     std::snprintf(b, sizeof(b), "n%d_b%d_%s_k%d_g%d", ctx->prm.n, ctx->batch,
