@@ -159,8 +159,8 @@ def ensemble_run(P, torch, args, weights):
     out["status"] = st_holder["st"]
     out["max_relres"] = max(max(i["pcg_relres"]) for i in st_holder["info"])
     out["pcg_iters_mean"] = float(np.mean([np.mean(i["pcg_iters"]) for i in st_holder["info"]]))
-    out["classes"] = [{k: c[k] for k in ("n", "members", "block", "cells_z", "cg_cells_z", "caps",
-                                         "rounds", "guess_mask")}
+    out["classes"] = [{k: c[k] for k in ("n", "members", "block", "cells_z", "cg_cells_z",
+                                         "tiled_cells_z", "caps", "rounds", "guess_mask")}
                       for c in E.classes()]
     log(f"ensemble graph: {out['ms_per_step']:.3f} ms/step, {out['value']:.4e} cell-steps/s")
 

@@ -238,6 +238,7 @@ typedef struct {
                                            the learned guess */
     int32_t cg_cells_z;                 /* planes per block of the CG kernel's z-march
                                            (0: its gathered form) */
+    int32_t tiled_cells_z;              /* ... of the other tiled z-marches (0: none) */
 } pisoc_ens_class;
 
 /* Workspace for the ensemble (0 if the members are invalid); 256-byte aligned. */
@@ -274,10 +275,11 @@ pisoc_status pisoc_ens_class_info(const pisoc_ens* ens, int32_t cls, pisoc_ens_c
  * at most 4096 blocks per member) on a representative set of the step's
  * kernels -- a predictor sweep, H/A, the corrector set-up, twelve CG
  * iterations and a dust sweep -- run on the systems of the last step, and
- * keeps the fastest; then, with that shape and where the CG kernel runs on
- * tiles, the planes per block of its z-march (its default, 8, 16 or 32).
- * Winners are cached in the JSON file cache_path (may be NULL) as [bx, cz, CG
- * planes (0: none)] under a key of grid size, members, precision, dust
+ * keeps the fastest; then, with that shape, the planes per block of the
+ * tiled z-marches and of the CG kernel's (each its default, 8, 16 or 32) where
+ * they run on tiles.  Winners are cached in the JSON file cache_path (may be
+ * NULL) as [bx, cz, CG planes, tile planes (0: none)] under a key of grid
+ * size, members, precision, dust
  * classes and guess; a cached entry is used without timing unless force != 0.
  * Needs one completed step.  Synchronises; the captured graph is rebuilt on
  * the next call. */

@@ -2779,7 +2779,7 @@ Launch make_launch(int n, int batch) {
     return make_launch_shaped(n, batch, bx, (n + nz - 1) / nz);
 }
 
-Launch make_tiled_launch(int n, int batch) {
+Launch make_tiled_launch(int n, int batch, int cz_tile) {
     Launch L{};
     if (n < 64 || n % kTX != 0 || n % kTY != 0) return L;   // nblocks = 0: not available
     const int gx = n / kTX, gy = n / kTY;
@@ -2787,6 +2787,7 @@ Launch make_tiled_launch(int n, int batch) {
     nz = nz < 1 ? 1 : nz;
     int cz = (n + nz - 1) / nz;
     if (cz < 8) cz = 8;
+    if (cz_tile > 0) cz = cz_tile < n ? cz_tile : n;
     nz = (n + cz - 1) / cz;
     L.block = dim3(kTX, kTY, 1);
     L.grid = dim3(gx, gy, nz * batch);

@@ -33,8 +33,9 @@ Launch make_launch_shaped(int n, int batch, int bx, int cz);
 
 // Launch of the LDS-tiled z-marching kernels (64 x 8 threads per block); nblocks
 // is 0 when n is not a multiple of the tile (64 x 8); at n = 64 one tile spans
-// x and its x halo wraps onto itself.
-Launch make_tiled_launch(int n, int batch = 1);
+// x and its x halo wraps onto itself.  Blocks march over at least 8 planes, or
+// exactly min(cz_tile, n) when cz_tile > 0 (a tuned choice).
+Launch make_tiled_launch(int n, int batch = 1, int cz_tile = 0);
 
 // Launch of the CG kernel for fields of elem_bytes per value.  For
 // n = 64 kRowCells and FP32: the full-row form, blocks of kRowWaves

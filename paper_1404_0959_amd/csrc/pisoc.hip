@@ -181,8 +181,10 @@ Layout make_layout(const pisoc_params* p, int batch) {
     const size_t es = p->precision == PISOC_FP64 ? sizeof(double) : sizeof(float);
     unsigned mb = std::max({make_launch(p->n, batch).nblocks, make_tiled_launch(p->n, batch).nblocks,
                             make_spmv_launch(p->n, batch, (int)es).nblocks});
-    for (int c : {8, 16, 32})   // the CG chunks the autotuner may choose
+    for (int c : {8, 16, 32}) {   // the chunks the autotuner may choose
         mb = std::max(mb, make_spmv_launch(p->n, batch, (int)es, c).nblocks);
+        mb = std::max(mb, make_tiled_launch(p->n, batch, c).nblocks);
+    }
     for (auto [bx, cz] : shape_candidates(p->n))
         mb = std::max(mb, make_launch_shaped(p->n, batch, bx, cz).nblocks);
     L.max_blocks = mb;
@@ -1260,8 +1262,9 @@ pisoc_status all_stats(pisoc_ctx* ctx, pisoc_stats* out) {
 // kernels -- a predictor sweep, H/A, the corrector set-up, kProbeCgIters CG
 // iterations and a dust sweep -- on the context's own buffers (all of them
 // scratch between steps; the persistent state is only read), and the fastest
-// wins; the CG kernel's tile z-chunk is then chosen the same way.  Winners
-// are kept in a small JSON object {"key": [bx, cz, CG planes], ...}.
+// wins; the tiled kernels' and the CG kernel's z-chunks are then chosen the
+// same way.  Winners are kept in a small JSON object
+// {"key": [bx, cz, CG planes, tile planes], ...}.
 std::string tune_key(const pisoc_ctx* ctx) {
     char b[96];
     std::snprintf(b, sizeof(b), "n%d_b%d_%s_k%d_g%d", ctx->prm.n, ctx->batch,
@@ -1270,16 +1273,17 @@ std::string tune_key(const pisoc_ctx* ctx) {
     return b;
 }
 
-// An entry is [block x, cells per thread along z, CG tile planes (0: the CG
-// kernel has no tile form at this size)].
-bool cache_lookup(const std::string& text, const std::string& key, int* bx, int* cz, int* cgz) {
+// An entry is [block x, cells per thread along z, CG tile planes, field tile
+// planes] (0: that kernel has no tile form at this size).
+bool cache_lookup(const std::string& text, const std::string& key, int* bx, int* cz, int* cgz,
+                  int* tlz) {
     const std::string pat = "\"" + key + "\"";
     size_t at = text.find(pat);
     if (at == std::string::npos) return false;
     at = text.find('[', at + pat.size());
     if (at == std::string::npos) return false;
-    return std::sscanf(text.c_str() + at, "[%d , %d , %d]", bx, cz, cgz) == 3 ||
-           std::sscanf(text.c_str() + at, "[%d,%d,%d]", bx, cz, cgz) == 3;
+    return std::sscanf(text.c_str() + at, "[%d , %d , %d , %d]", bx, cz, cgz, tlz) == 4 ||
+           std::sscanf(text.c_str() + at, "[%d,%d,%d,%d]", bx, cz, cgz, tlz) == 4;
 }
 
 std::string read_file(const char* path) {
@@ -1295,9 +1299,9 @@ std::string read_file(const char* path) {
 }
 
 // Rewrite the cache with the entry for key replaced or added.
-bool cache_store(const char* path, const std::string& key, int bx, int cz, int cgz) {
+bool cache_store(const char* path, const std::string& key, int bx, int cz, int cgz, int tlz) {
     std::string text = read_file(path);
-    std::vector<std::pair<std::string, std::array<int, 3>>> entries;
+    std::vector<std::pair<std::string, std::array<int, 4>>> entries;
     size_t pos = 0;
     for (;;) {
         const size_t q0 = text.find('"', pos);
@@ -1305,18 +1309,20 @@ bool cache_store(const char* path, const std::string& key, int bx, int cz, int c
         const size_t q1 = text.find('"', q0 + 1);
         if (q1 == std::string::npos) break;
         const std::string k = text.substr(q0 + 1, q1 - q0 - 1);
-        int a, b, c;
-        if (cache_lookup(text.substr(q0), k, &a, &b, &c) && k != key) entries.push_back({k, {a, b, c}});
+        int a, b, c, d;
+        if (cache_lookup(text.substr(q0), k, &a, &b, &c, &d) && k != key)
+            entries.push_back({k, {a, b, c, d}});
         pos = text.find(']', q1);
         if (pos == std::string::npos) break;
     }
-    entries.push_back({key, {bx, cz, cgz}});
+    entries.push_back({key, {bx, cz, cgz, tlz}});
     FILE* f = std::fopen(path, "wb");
     if (!f) return false;
     std::fprintf(f, "{\n");
     for (size_t i = 0; i < entries.size(); ++i)
-        std::fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", entries[i].first.c_str(), entries[i].second[0],
-                     entries[i].second[1], entries[i].second[2], i + 1 < entries.size() ? "," : "");
+        std::fprintf(f, "  \"%s\": [%d, %d, %d, %d]%s\n", entries[i].first.c_str(),
+                     entries[i].second[0], entries[i].second[1], entries[i].second[2],
+                     entries[i].second[3], i + 1 < entries.size() ? "," : "");
     std::fprintf(f, "}\n");
     std::fclose(f);
     return true;
@@ -1352,29 +1358,42 @@ void set_cg_chunk(pisoc_ctx* ctx, int cgz) {
 // Only the tile form of the CG kernel takes a tuned z-chunk.
 bool cg_tunable(const pisoc_ctx* ctx) { return ctx->TS.nblocks && ctx->TS.v == 0; }
 
-// The default chunk, then 8, 16 and 32 planes (at most n), each once.
-std::vector<int> cg_chunk_candidates(const pisoc_ctx* ctx) {
-    std::vector<int> out{make_spmv_launch(ctx->prm.n, ctx->batch, (int)ctx->es).cz};
+// The default chunk d0, then 8, 16 and 32 planes (at most n), each once.
+std::vector<int> chunk_candidates(int n, int d0) {
+    std::vector<int> out{d0};
     for (int c : {8, 16, 32})
-        if (c <= ctx->prm.n && std::find(out.begin(), out.end(), c) == out.end()) out.push_back(c);
+        if (c <= n && std::find(out.begin(), out.end(), c) == out.end()) out.push_back(c);
     return out;
+}
+std::vector<int> cg_chunk_candidates(const pisoc_ctx* ctx) {
+    return chunk_candidates(ctx->prm.n, make_spmv_launch(ctx->prm.n, ctx->batch, (int)ctx->es).cz);
+}
+
+// The same for the tiled field kernels' launch.
+void set_tl_chunk(pisoc_ctx* ctx, int tlz) { ctx->TL = make_tiled_launch(ctx->prm.n, ctx->batch, tlz); }
+bool tl_tunable(const pisoc_ctx* ctx) { return ctx->TL.nblocks != 0; }
+std::vector<int> tl_chunk_candidates(const pisoc_ctx* ctx) {
+    return chunk_candidates(ctx->prm.n, make_tiled_launch(ctx->prm.n, ctx->batch).cz);
 }
 
 // Launch shapes of one size class: the gathered kernels' block and cells per
-// thread (timed over the shape candidates), then, with that shape, the CG
-// kernel's tile z-chunk (timed over cg_chunk_candidates), each by the probe
-// step; or the cached choice.
+// thread (timed over the shape candidates), then, with that shape, the tiled
+// field kernels' z-chunk and last the CG kernel's tile z-chunk (each timed
+// over its chunk candidates), each by the probe step; or the cached choice.
 pisoc_status tune_ctx(pisoc_ctx* ctx, const char* cache_path, int force, int* bx_out, int* cz_out) {
     const std::string key = tune_key(ctx);
-    const bool cgt = cg_tunable(ctx);
-    int bx = 0, cz = 0, cgz = 0;
-    if (!force && cache_lookup(read_file(cache_path), key, &bx, &cz, &cgz)) {
-        bool ok = false, okc = !cgt && cgz == 0;
+    const bool cgt = cg_tunable(ctx), tlt = tl_tunable(ctx);
+    int bx = 0, cz = 0, cgz = 0, tlz = 0;
+    if (!force && cache_lookup(read_file(cache_path), key, &bx, &cz, &cgz, &tlz)) {
+        bool ok = false, okc = !cgt && cgz == 0, okt = !tlt && tlz == 0;
         for (auto [a, b] : shape_candidates(ctx->prm.n)) ok = ok || (a == bx && b == cz);
         if (cgt)
             for (int c : cg_chunk_candidates(ctx)) okc = okc || c == cgz;
-        if (ok && okc) {
+        if (tlt)
+            for (int c : tl_chunk_candidates(ctx)) okt = okt || c == tlz;
+        if (ok && okc && okt) {
             set_shape(ctx, make_launch_shaped(ctx->prm.n, ctx->batch, bx, cz));
+            if (tlt) set_tl_chunk(ctx, tlz);
             if (cgt) set_cg_chunk(ctx, cgz);
             *bx_out = bx;
             *cz_out = cz;
@@ -1401,7 +1420,7 @@ pisoc_status tune_ctx(pisoc_ctx* ctx, const char* cache_path, int force, int* bx
         return hipEventElapsedTime(&ms, e0, e1) == hipSuccess ? ms : -1.f;
     };
     float best = 1e30f;
-    int best_bx = 0, best_cz = 0, best_cgz = 0;
+    int best_bx = 0, best_cz = 0, best_cgz = 0, best_tlz = 0;
     const Launch L0 = ctx->L;
     for (auto [a, b] : shape_candidates(ctx->prm.n)) {
         set_shape(ctx, make_launch_shaped(ctx->prm.n, ctx->batch, a, b));
@@ -1414,6 +1433,19 @@ pisoc_status tune_ctx(pisoc_ctx* ctx, const char* cache_path, int force, int* bx
         }
     }
     if (best_bx != 0) set_shape(ctx, make_launch_shaped(ctx->prm.n, ctx->batch, best_bx, best_cz));
+    if (best_bx != 0 && tlt) {
+        float best_t = 1e30f;
+        for (int c : tl_chunk_candidates(ctx)) {
+            set_tl_chunk(ctx, c);
+            const float ms = time_probe();
+            if (ms < 0.f) break;
+            if (ms < best_t) {
+                best_t = ms;
+                best_tlz = c;
+            }
+        }
+        set_tl_chunk(ctx, best_tlz);
+    }
     if (best_bx != 0 && cgt) {
         float best_c = 1e30f;
         for (int c : cg_chunk_candidates(ctx)) {
@@ -1431,13 +1463,14 @@ pisoc_status tune_ctx(pisoc_ctx* ctx, const char* cache_path, int force, int* bx
     (void)hipEventDestroy(e1);
     ctx->prof.on = prof;
     HIP_TRY(ctx, hipGetLastError());
-    if (best_bx == 0 || (cgt && best_cgz == 0)) {
+    if (best_bx == 0 || (cgt && best_cgz == 0) || (tlt && best_tlz == 0)) {
         set_shape(ctx, L0);
+        if (tlt) set_tl_chunk(ctx, 0);
         if (cgt) set_cg_chunk(ctx, 0);
         ctx->err = "no launch shape could be timed";
         return PISOC_ERR_HIP;
     }
-    if (cache_path && !cache_store(cache_path, key, best_bx, best_cz, best_cgz)) {
+    if (cache_path && !cache_store(cache_path, key, best_bx, best_cz, best_cgz, best_tlz)) {
         ctx->err = std::string("cannot write ") + cache_path;
         return PISOC_ERR_INVALID;
     }
@@ -1942,6 +1975,7 @@ pisoc_status pisoc_ens_class_info(const pisoc_ens* e, int32_t cls, pisoc_ens_cla
         if (ctx->prm.guess == PISOC_GUESS_LEARNED && (!audit_on(ctx) || ctx->audit.use[c]))
             o.guess_mask |= 1 << c;
     o.cg_cells_z = ctx->TS.nblocks ? ctx->TS.cz : 0;
+    o.tiled_cells_z = ctx->TL.nblocks ? ctx->TL.cz : 0;
     *h_out = o;
     return PISOC_OK;
 }

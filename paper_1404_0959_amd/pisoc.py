@@ -82,7 +82,7 @@ class EnsClass(C.Structure):
     _fields_ = [("n", C.c_int32), ("members", C.c_int32), ("block_x", C.c_int32),
                 ("block_y", C.c_int32), ("cells_z", C.c_int32), ("blocks", C.c_int32),
                 ("caps", C.c_int32 * MAX_CORR), ("cap_later", C.c_int32), ("rounds", C.c_int32),
-                ("guess_mask", C.c_int32), ("cg_cells_z", C.c_int32)]
+                ("guess_mask", C.c_int32), ("cg_cells_z", C.c_int32), ("tiled_cells_z", C.c_int32)]
 
 
 class KernelStat(C.Structure):
@@ -412,7 +412,7 @@ class Ensemble:
             out.append(dict(n=e.n, members=e.members, block=(e.block_x, e.block_y),
                             cells_z=e.cells_z, blocks=e.blocks, caps=list(e.caps),
                             cap_later=e.cap_later, rounds=e.rounds, guess_mask=e.guess_mask,
-                            cg_cells_z=e.cg_cells_z))
+                            cg_cells_z=e.cg_cells_z, tiled_cells_z=e.tiled_cells_z))
         return out
 
     def fields(self, m, which):

@@ -251,7 +251,7 @@ def test_autotune_cache_round_trip(P, tmp_path):
     for c in cl:
         key = [k for k in cache if k.startswith(f"n{c['n']}_b{c['members']}_fp64")]
         assert len(key) == 1
-        assert cache[key[0]] == [c["block"][0], c["cells_z"], c["cg_cells_z"]]
+        assert cache[key[0]] == [c["block"][0], c["cells_z"], c["cg_cells_z"], c["tiled_cells_z"]]
     # tuned shapes still give converged, mass-conserving steps (graph mode)
     m0 = [s["mass_gas"] for s in e.stats()]
     st, info = e.step(3, mode=P.ENS_GRAPH)
@@ -263,6 +263,6 @@ def test_autotune_cache_round_trip(P, tmp_path):
     e2 = P.Ensemble(cs, **kw)
     e2.step(1, mode=P.ENS_EAGER)
     e2.autotune(path)
-    assert [(c["block"], c["cells_z"], c["cg_cells_z"]) for c in e2.classes()] == \
-        [(c["block"], c["cells_z"], c["cg_cells_z"]) for c in cl]
+    key_of = lambda c: (c["block"], c["cells_z"], c["cg_cells_z"], c["tiled_cells_z"])
+    assert [key_of(c) for c in e2.classes()] == [key_of(c) for c in cl]
     assert json.load(open(path)) == cache
