@@ -218,11 +218,14 @@ int32_t pisoc_profile_read(const pisoc_ctx* ctx, pisoc_kernel_stat* h_out, int32
  * step is committed on the device.  The first captured call begins with one
  * eager step that measures those iterations (two where a class audits its
  * learned guess and has not yet measured both choices; a call too short for
- * them returns before capturing, and the next one goes on).  A solve that reaches its cap
- * without converging flags PISOC_FLAG_PCG_MAXIT (status
- * PISOC_WARN_NOT_CONVERGED, the state has advanced); the caps then grow and the
- * graph is captured again on the next call.  A diverged member cannot be rolled
- * back in this mode (PISOC_ERR_DIVERGED after the fact). */
+ * them returns before capturing, and the next one goes on).  The caps follow
+ * the iterations the members need (they grow as the flow decays): when a call
+ * ends with a solve within 2 iterations of the caps its graph holds, the
+ * graphs are captured again at once with the new caps.  A solve that reaches
+ * its cap without converging flags PISOC_FLAG_PCG_MAXIT (status
+ * PISOC_WARN_NOT_CONVERGED, the state has advanced); the caps then grow by
+ * half and the graphs are captured again at once.  A diverged member cannot be
+ * rolled back in this mode (PISOC_ERR_DIVERGED after the fact). */
 typedef struct pisoc_ens pisoc_ens;
 
 enum { PISOC_ENS_EAGER = 0, PISOC_ENS_GRAPH = 1 };

@@ -252,9 +252,12 @@ struct pisoc_ctx {
     int pred_first[PISOC_MAX_CORR];  // CG iterations of the last first solve (all members)
     int pred_later;                  // ... of the last later refinement round
     // captured mode: CG pairs per first solve, per later round, refinement rounds
+    // (tracked over the steps), and those the current graphs were built with
     int caps[PISOC_MAX_CORR];
     int cap_later;
     int rounds;
+    int caps_built[PISOC_MAX_CORR];
+    int cap_later_built;
     size_t es;      // bytes per field element (8 or 4)
     // learned-guess audit of eager steps (guess_audit > 0): running means of the
     // CG iterations of each corrector's solve with and without the guess, and
@@ -1560,6 +1563,10 @@ pisoc_status build_graphs(pisoc_ens* e) {
         }
         for (pisoc_ctx* ctx : e->cls) rotate(ctx);
     }
+    for (pisoc_ctx* ctx : e->cls) {
+        std::copy(ctx->caps, ctx->caps + PISOC_MAX_CORR, ctx->caps_built);
+        ctx->cap_later_built = ctx->cap_later;
+    }
     e->built = true;
     e->parity = 0;
     return PISOC_OK;
@@ -1873,7 +1880,7 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
         }
         pisoc_status st = ens_sync(e);
         if (st != PISOC_OK) return st;
-        bool regrow_any = false, bad = false, bad_dt = false;
+        bool regrow_any = false, near_any = false, bad = false, bad_dt = false;
         for (size_t c = 0; c < e->cls.size(); ++c) {
             pisoc_ctx* ctx = e->cls[c];
             int first[PISOC_MAX_CORR] = {0, 0, 0, 0};
@@ -1904,8 +1911,20 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
             }
             set_caps(ctx, first, later, ctx->rounds - 1);
             regrow_any = regrow_any || regrow;
+            // the iterations have come within 2 of the caps the graphs hold
+            // (they grow as the flow decays): capture again with the tracked
+            // caps before a solve runs into them
+            for (int q = 0; q < ctx->prm.n_corr; ++q)
+                if (first[q] + 2 > ctx->caps_built[q]) near_any = true;
+            if (ctx->rounds > 1 && later > 0 && later + 2 > ctx->cap_later_built) near_any = true;
         }
-        if (regrow_any) drop_graphs(e);
+        if ((regrow_any || near_any) && !bad && !bad_dt) {
+            // a capture needs no eager step here: the caps are known
+            pisoc_status bs = build_graphs(e);
+            if (bs != PISOC_OK) return bs;
+        } else if (regrow_any) {
+            drop_graphs(e);
+        }
         if (bad_dt) {
             e->err = "time step undefined or non-positive in a member";
             if (h_info) std::copy(rec.begin(), rec.end(), h_info);
@@ -1969,8 +1988,8 @@ pisoc_status pisoc_ens_class_info(const pisoc_ens* e, int32_t cls, pisoc_ens_cla
     o.cells_z = ctx->L.cz;
     o.blocks = (int32_t)ctx->L.nblocks;
     o.rounds = ctx->rounds;
-    o.cap_later = ctx->cap_later;
-    for (int c = 0; c < PISOC_MAX_CORR; ++c) o.caps[c] = ctx->caps[c];
+    o.cap_later = e->built ? ctx->cap_later_built : ctx->cap_later;
+    for (int c = 0; c < PISOC_MAX_CORR; ++c) o.caps[c] = e->built ? ctx->caps_built[c] : ctx->caps[c];
     for (int c = 0; c < ctx->prm.n_corr; ++c)
         if (ctx->prm.guess == PISOC_GUESS_LEARNED && (!audit_on(ctx) || ctx->audit.use[c]))
             o.guess_mask |= 1 << c;
