@@ -236,6 +236,30 @@ def test_bench_ensemble_configuration(P, tmp_path):
     E.close()
 
 
+def test_graph_caps_follow_iterations(P):
+    """Captured FP32 steps over a decaying flow: the CG iterations grow from
+    step to step, and the graphs are captured again before a solve reaches
+    the caps they hold, so no call in 120 steps reports a solve stopped at a
+    cap (PISOC_FLAG_PCG_MAXIT) and every solve meets the tolerance."""
+    cs = [make_hit_case(32, 31, mach=0.2, stokes=(0.2,)),
+          make_hit_case(32, 32, mach=0.5, stokes=(0.4,)),
+          make_hit_case(48, 33, mach=0.2, stokes=(0.1,))]
+    kw = dict(p_tol=1e-6, precision=P.FP32_REFINED, inner_tol=1e-6)
+    E = P.Ensemble(cs, **kw)
+    first_caps = None
+    for call in range(12):
+        st, info = E.step(10, mode=P.ENS_GRAPH)
+        assert st == P.OK, (call, st, [i["flags"] for i in info])
+        for m, i in enumerate(info):
+            assert max(i["pcg_relres"]) <= 1e-6, (call, m, i)
+            assert not i["flags"] & P.FLAG_PCG_MAXIT, (call, m, i)
+        caps = [c["caps"][:2] for c in E.classes()]
+        first_caps = first_caps or caps
+    assert E.steps_done == 120
+    print("caps", first_caps, "->", caps)
+    E.close()
+
+
 def test_autotune_cache_round_trip(P, tmp_path):
     cs = cases()
     kw = dict(p_tol=1e-8)
