@@ -99,3 +99,38 @@ def test_workspace_checked_before_gpu_work(lib):
 def test_status_strings(lib):
     for st in (0, 1, 2, -1, -2, -3, -4):
         assert lib.pisoc_status_string(st)
+
+
+# C structs of the header and their ctypes mirrors in the binding
+STRUCTS = {"pisoc_params": P.Params, "pisoc_step_info": P.StepInfo, "pisoc_stats": P.Stats,
+           "pisoc_ens_class": P.EnsClass, "pisoc_kernel_stat": P.KernelStat}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every struct the binding passes across the ABI has the header's size
+    and field offsets (compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pisoc.h"', "int main(void) {"]
+    for cname, py in STRUCTS.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n"):
+        if line:
+            cname, field, value = line.split()
+            got[(cname, field)] = int(value)
+    for cname, py in STRUCTS.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
