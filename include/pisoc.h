@@ -220,8 +220,8 @@ int32_t pisoc_profile_read(const pisoc_ctx* ctx, pisoc_kernel_stat* h_out, int32
  * learned guess and has not yet measured both choices; a call too short for
  * them returns before capturing, and the next one goes on).  The caps follow
  * the iterations the members need (they grow as the flow decays): when a call
- * ends with a solve within 2 iterations of the caps its graph holds, the
- * graphs are captured again at once with the new caps.  A solve that reaches
+ * ends with a solve within 10 % + 2 iterations of the caps its graph holds,
+ * the graphs are captured again at once with the new caps.  A solve that reaches
  * its cap without converging flags PISOC_FLAG_PCG_MAXIT (status
  * PISOC_WARN_NOT_CONVERGED, the state has advanced); the caps then grow by
  * half and the graphs are captured again at once.  A diverged member cannot be

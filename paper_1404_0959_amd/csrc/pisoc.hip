@@ -1911,12 +1911,14 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
             }
             set_caps(ctx, first, later, ctx->rounds - 1);
             regrow_any = regrow_any || regrow;
-            // the iterations have come within 2 of the caps the graphs hold
-            // (they grow as the flow decays): capture again with the tracked
-            // caps before a solve runs into them
+            // the iterations have come within 10 % + 2 of the caps the graphs
+            // hold (they grow as the flow decays, by several within a long
+            // call): capture again with the tracked caps (+25 % + 2) before a
+            // solve runs into them
+            auto near = [](int it, int cap) { return (int)std::ceil(1.1 * it) + 2 > cap; };
             for (int q = 0; q < ctx->prm.n_corr; ++q)
-                if (first[q] + 2 > ctx->caps_built[q]) near_any = true;
-            if (ctx->rounds > 1 && later > 0 && later + 2 > ctx->cap_later_built) near_any = true;
+                if (near(first[q], ctx->caps_built[q])) near_any = true;
+            if (ctx->rounds > 1 && later > 0 && near(later, ctx->cap_later_built)) near_any = true;
         }
         if ((regrow_any || near_any) && !bad && !bad_dt) {
             // a capture needs no eager step here: the caps are known
