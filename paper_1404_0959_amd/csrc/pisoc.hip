@@ -1923,7 +1923,11 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
         if ((regrow_any || near_any) && !bad && !bad_dt) {
             // a capture needs no eager step here: the caps are known
             pisoc_status bs = build_graphs(e);
-            if (bs != PISOC_OK) return bs;
+            if (bs != PISOC_OK) {
+                // the steps of this call stand; their records go out with the error
+                if (h_info) std::copy(rec.begin(), rec.end(), h_info);
+                return bs;
+            }
         } else if (regrow_any) {
             drop_graphs(e);
         }
