@@ -48,9 +48,11 @@ typedef enum {
     PISOC_OK = 0,
     PISOC_WARN_NOT_CONVERGED = 1, /* a pressure solve hit p_maxit (state advanced) */
     PISOC_WARN_GUESS_FALLBACK = 2, /* learned guess rejected, zero guess used */
+    PISOC_WARN_DUST = 3,           /* PISOC_FLAG_DUST_NEG or _DUST_DIAG raised (state advanced) */
     PISOC_ERR_INVALID = -1,        /* bad argument, or dt undefined/non-positive */
     PISOC_ERR_HIP = -2,            /* a HIP runtime call failed */
-    PISOC_ERR_DIVERGED = -3,       /* non-finite or non-positive density; step rejected */
+    PISOC_ERR_DIVERGED = -3,       /* non-finite or non-positive gas density, non-finite
+                                      field or dust density; step rejected */
     PISOC_ERR_WORKSPACE = -4       /* workspace missing, too small or misaligned */
 } pisoc_status;
 
@@ -74,7 +76,16 @@ enum {
     PISOC_FLAG_RHO_NONPOS = 4,
     PISOC_FLAG_GUESS_FALLBACK = 8,
     PISOC_FLAG_BAD_DT = 16,
-    PISOC_FLAG_GUESS_SKIPPED = 32
+    PISOC_FLAG_GUESS_SKIPPED = 32,
+    /* Dust transport of the Equilibrium-Eulerian model (Results section), any
+     * class.  The central fourth-order fluxes are not monotone, so a bulk
+     * density can undershoot below zero near sharp concentration fronts: */
+    PISOC_FLAG_DUST_NEG = 64,       /* some rho_j < 0 after the step (PISOC_WARN_DUST) */
+    PISOC_FLAG_DUST_NONFINITE = 128,/* a non-finite rho_j (PISOC_ERR_DIVERGED) */
+    /* the diagonal rho^{n+1}/dt + (9/16) div G of the implicit mass-ratio
+     * equation is <= 0 in some cell: the drift compresses the dust faster than
+     * the equation's Jacobi sweeps can follow (PISOC_WARN_DUST) */
+    PISOC_FLAG_DUST_DIAG = 256
 };
 
 typedef struct {
@@ -98,7 +109,8 @@ typedef struct {
     double inner_tol;          /* FP32_REFINED: relative tolerance of each inner FP32 solve */
     int32_t max_refine;        /* FP32_REFINED: cap on FP64 refinement rounds per solve */
     int32_t capture;           /* != 0: keep corrector-1 pressure system of the last step
-                                  (b, p', p0, diag) for pisoc_fields */
+                                  (b, p', p0, diag, w, and with the learned guess g and
+                                  x0) and the predictor's u* for pisoc_fields */
     int32_t guess_audit;       /* learned guess, pisoc_step: 0 = apply it to every solve;
                                   k > 0 = apply it to a corrector's solve only while the CG
                                   iterations it saves (running means of solves with and
@@ -140,15 +152,28 @@ enum {
     PISOC_FIELD_PSOLVE_B = 1u << 5, /* captured: right-hand side b (needs capture) */
     PISOC_FIELD_PSOLVE_X = 1u << 6, /* captured: solution p' */
     PISOC_FIELD_P_PREV = 1u << 7,   /* captured: p(rho) at the corrector's start */
-    PISOC_FIELD_PSOLVE_DIAG = 1u << 8 /* captured: diagonal of the pressure operator */
+    PISOC_FIELD_PSOLVE_DIAG = 1u << 8, /* captured: diagonal of the pressure operator */
+    PISOC_FIELD_USTAR = 1u << 9,    /* captured: 3 n^3, the momentum predictor's output u* */
+    PISOC_FIELD_GUESS = 1u << 10,   /* captured, learned guess: the network's guess g of
+                                       corrector 1's solve (s1 times its output) */
+    PISOC_FIELD_GUESS_X0 = 1u << 11,/* captured, learned guess: that solve's start x0 =
+                                       alpha g, alpha = g.b / g.(M g), or 0 on a fallback */
+    PISOC_FIELD_PSOLVE_W = 1u << 12 /* captured: w = rho/a_P, whose I4 face values are the
+                                       operator's K_f (with diag, M is then known:
+                                       psi/dt = diag - (1/h^2) sum_f K_f) */
 };
 
 /* Bytes of device workspace pisoc_init needs for these parameters (0 if the
  * parameters are invalid).  The workspace must be 256-byte aligned. */
 size_t pisoc_workspace_bytes(const pisoc_params* prm);
 
-/* Validate prm, lay out the workspace, convert the initial state and compute
- * the initial face mass fluxes phi = I4(rho) I4(u_d) A.
+/* Set up one simulation of the paper's problem statement (Introduction: freely
+ * decaying homogeneous isotropic turbulence in the subsonic regime; Results:
+ * barotropic closure p = C rho^gamma of the second footnote, dust classes of
+ * the Equilibrium-Eulerian model with response times tau_p from the Stokes
+ * law): validate prm, lay out the workspace, convert the initial state and
+ * compute the initial face mass fluxes phi = I4(rho) I4(u_d) A with the
+ * fourth-order central interpolation I4 of the Results section.
  * d_rho: n^3 FP64, d_u: 3 n^3 FP64 (SoA), d_rho_p: n_classes n^3 FP64 dust bulk
  * densities (may be NULL when n_classes = 0).  The inputs are copied; the
  * caller may free them afterwards.  On success *out receives a context that
@@ -157,14 +182,23 @@ pisoc_status pisoc_init(const pisoc_params* prm, void* d_workspace, size_t ws_by
                         const double* d_rho, const double* d_u, const double* d_rho_p,
                         void* hip_stream, pisoc_ctx** out);
 
-/* Advance n_steps time steps.  h_info (host, may be NULL) receives one record
- * per completed step.  Synchronises the stream before returning.  On an error
+/* Advance n_steps time steps of the Results section's scheme: the PISO
+ * pressure-based step (adaptive time step, density predictor, momentum
+ * predictor, n_corr pressure correctors with fourth-order central
+ * interpolation), then each dust class transported with the Equilibrium-
+ * Eulerian particle velocity u_p = u - tau_p Du/Dt (first order in the Stokes
+ * number; tau_p = 0 is the dusty gas of the third footnote).  h_info (host, may
+ * be NULL) receives one record per completed step.  Synchronises the stream before returning.  On an error
  * the state stays at the last completed step and the number of completed steps
  * is available from pisoc_steps_done. */
 pisoc_status pisoc_step(pisoc_ctx* ctx, int32_t n_steps, pisoc_step_info* h_info);
 
-/* Copy selected fields out as FP64, one destination per set bit of `which`, in
- * increasing bit order (d_dst[0] for the lowest set bit).  Asynchronous. */
+/* Copy selected fields of the current state out as FP64: the gas density,
+ * velocity and face mass fluxes, the dust bulk densities and the barotropic
+ * pressure C rho^gamma (second footnote of the Results section), and, with
+ * params.capture, corrector 1's pressure system of the last step.  One
+ * destination per set bit of `which`, in increasing bit order (d_dst[0] for
+ * the lowest set bit), each sized as its selector states.  Asynchronous. */
 pisoc_status pisoc_fields(pisoc_ctx* ctx, uint32_t which, double* const* d_dst);
 
 /* Volume statistics of the current state (FP64 reductions; synchronises). */
@@ -247,9 +281,12 @@ typedef struct {
 /* Workspace for the ensemble (0 if the members are invalid); 256-byte aligned. */
 size_t pisoc_ens_workspace_bytes(const pisoc_params* h_members, int32_t count);
 
-/* As pisoc_init for `count` members: h_members[m] their parameters, and host
- * arrays of device pointers d_rho[m], d_u[m], d_rho_p[m] (d_rho_p may be NULL
- * without dust).  The set-up waits for work already on hip_stream. */
+/* The batch initialisation: as pisoc_init (the same problem statement of the
+ * Introduction and Results section, one independent realisation per member)
+ * for `count` members: h_members[m] their parameters, and host arrays of
+ * device pointers d_rho[m], d_u[m], d_rho_p[m] (d_rho_p may be NULL without
+ * dust).  The set-up waits for work already on hip_stream.  Errors as
+ * pisoc_init; on an error no ensemble is created. */
 pisoc_status pisoc_ens_init(const pisoc_params* h_members, int32_t count, void* d_workspace,
                             size_t ws_bytes, const double* const* d_rho, const double* const* d_u,
                             const double* const* d_rho_p, void* hip_stream, pisoc_ens** out);

@@ -15,13 +15,15 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "conv.c")]
+SOURCES = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "conv.c"),
+           os.path.join(HERE, "guess.c")]
 
 MAX_CLASSES = 8
 MAX_CORR = 8
 
-OK, WARN_NOT_CONVERGED, ERR_INVALID, ERR_DIVERGED = 0, 1, -1, -3
+OK, WARN_NOT_CONVERGED, WARN_DUST, ERR_INVALID, ERR_DIVERGED = 0, 1, 3, -1, -3
 FLAG_PCG_MAXIT, FLAG_NONFINITE, FLAG_RHO_NONPOS, FLAG_KFACE_NONPOS = 1, 2, 4, 8
+FLAG_DUST_NEG, FLAG_DUST_NONFINITE, FLAG_DUST_DIAG = 64, 128, 256
 
 RHO, U, PHI, RHO_P, P = 0, 1, 2, 3, 4
 SYS_B, SYS_W, SYS_PSIDT, SYS_K, SYS_X, SYS_P0, SYS_DIAG, SYS_USTAR = 10, 11, 12, 13, 14, 15, 16, 17
@@ -103,6 +105,10 @@ def lib():
         L.ora_pcg.restype = C.c_int32
         if hasattr(L, "ora_conv_forward"):
             _bind_conv(L)
+        L.ora_net_inputs.argtypes = [C.c_int32, dp, dp, dp, dp, dp]
+        L.ora_net_inputs.restype = C.c_int
+        L.ora_guess_start.argtypes = [C.c_int32, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.ora_guess_start.restype = C.c_int
         _lib = L
     return _lib
 
@@ -180,6 +186,32 @@ def pcg(psidt, K, b, x0=None, tol=1e-10, maxit=1000):
     it = lib().ora_pcg(b.shape[0], _p(psidt), _p(K[0]), _p(K[1]), _p(K[2]), _p(b), _p(x),
                        tol, maxit, C.byref(rel))
     return x, int(it), rel.value
+
+
+# ---------------------------------------------------------------- learned guess
+def net_inputs(b, diag, p0):
+    """Network inputs [n^3][2] ((b/diag)/s1, (p0 - <p0>)/s2) and (s1, s2)."""
+    b = _f64(b); diag = _f64(diag); p0 = _f64(p0)
+    n = b.shape[0]
+    x = np.empty((n ** 3, 2))
+    sc = np.empty(2)
+    st = lib().ora_net_inputs(n, _p(b), _p(diag), _p(p0), _p(x), _p(sc))
+    if st != OK:
+        raise ValueError(f"ora_net_inputs failed with status {st}")
+    return x, (float(sc[0]), float(sc[1]))
+
+
+def guess_start(psidt, K, b, g):
+    """Solve start from the guess g: (x0, alpha, ||b - alpha M g|| / ||b||, fell_back)."""
+    psidt = _f64(psidt); K = [_f64(k) for k in K]; b = _f64(b); g = _f64(g)
+    x0 = np.empty_like(b)
+    a = C.c_double(0.0)
+    rr = C.c_double(0.0)
+    st = lib().ora_guess_start(b.shape[0], _p(psidt), _p(K[0]), _p(K[1]), _p(K[2]), _p(b), _p(g),
+                               _p(x0), C.byref(a), C.byref(rr))
+    if st < 0:
+        raise ValueError(f"ora_guess_start failed with status {st}")
+    return x0, a.value, rr.value, bool(st)
 
 
 # ---------------------------------------------------------------- conv net

@@ -658,6 +658,9 @@ static int one_step(ora_state* s, ora_info* info) {
             for (int d = 0; d < 3; ++d)
                 for (size_t P = 0; P < N; ++P) G[d][P] = phin[d][P] - tau * Dfa[d][P];
             ora_div_flux(n, G[0], G[1], G[2], divG);
+            /* the diagonal of the implicit equation below must stay positive */
+            for (size_t P = 0; P < N; ++P)
+                if (!(rhok[P] / dt + (9.0 / 16.0) * divG[P] > 0.0)) flags |= ORA_FLAG_DUST_DIAG;
             for (size_t P = 0; P < N; ++P) Y[P] = rj[P] / s->rho[P];
             /* implicit Euler for rho Y: Jacobi sweeps */
             for (int sweep = 0; sweep < pr->n_dust_sweeps; ++sweep) {
@@ -681,7 +684,11 @@ static int one_step(ora_state* s, ora_info* info) {
             }
             ora_div_flux(n, tface[0], tface[1], tface[2], ry);
             rpn[c] = pool_get(s, slot++);
-            for (size_t P = 0; P < N; ++P) rpn[c][P] = rj[P] - dt * ry[P];
+            for (size_t P = 0; P < N; ++P) {
+                rpn[c][P] = rj[P] - dt * ry[P];
+                if (!isfinite(rpn[c][P])) flags |= ORA_FLAG_DUST_NONFINITE;
+                else if (rpn[c][P] < 0.0) flags |= ORA_FLAG_DUST_NEG;
+            }
         }
     }
 
@@ -698,9 +705,11 @@ static int one_step(ora_state* s, ora_info* info) {
     info->courant = sigma * dt;
     info->flags = flags;
     info->mass_gas = m_gas;
-    if (flags & (ORA_FLAG_NONFINITE | ORA_FLAG_RHO_NONPOS)) {
+    if (flags & (ORA_FLAG_NONFINITE | ORA_FLAG_RHO_NONPOS | ORA_FLAG_DUST_NONFINITE)) {
         status = ORA_ERR_DIVERGED;
     } else {
+        if ((flags & (ORA_FLAG_DUST_NEG | ORA_FLAG_DUST_DIAG)) && status == ORA_OK)
+            status = ORA_WARN_DUST;
         memcpy(s->rho, rhok, N * sizeof(double));
         for (int d = 0; d < 3; ++d) {
             memcpy(s->u[d], ucur[d], N * sizeof(double));
@@ -726,7 +735,11 @@ int ora_step(ora_state* s, int32_t n_steps, ora_info* info) {
         ora_info local;
         int st = one_step(s, info ? &info[i] : &local);
         if (st < 0) return st;
-        if (st > worst) worst = st;
+        /* a solve that hit its cap outranks the dust warnings, as in the GPU library */
+        if (st == ORA_WARN_NOT_CONVERGED || worst == ORA_WARN_NOT_CONVERGED)
+            worst = ORA_WARN_NOT_CONVERGED;
+        else if (st > worst)
+            worst = st;
     }
     return worst;
 }

@@ -26,6 +26,7 @@ extern "C" {
 /* status codes (same meaning as the GPU library's) */
 #define ORA_OK 0
 #define ORA_WARN_NOT_CONVERGED 1
+#define ORA_WARN_DUST 3            /* a dust flag below (negative density, diagonal) */
 #define ORA_ERR_INVALID (-1)
 #define ORA_ERR_DIVERGED (-3)
 
@@ -34,6 +35,14 @@ extern "C" {
 #define ORA_FLAG_NONFINITE 2
 #define ORA_FLAG_RHO_NONPOS 4
 #define ORA_FLAG_KFACE_NONPOS 8
+/* dust (Equilibrium-Eulerian transport, per step, any class):
+ * a bulk density rho_j < 0 after the conservative finish (warning) */
+#define ORA_FLAG_DUST_NEG 64
+/* a non-finite rho_j (the step is rejected) */
+#define ORA_FLAG_DUST_NONFINITE 128
+/* the implicit mass-ratio equation's diagonal rho^{n+1}/dt + (9/16) div G is
+ * <= 0 in some cell (its Jacobi sweeps lose their contraction there; warning) */
+#define ORA_FLAG_DUST_DIAG 256
 
 typedef struct {
     int32_t n;
@@ -110,6 +119,13 @@ void ora_helm_apply(int32_t n, const double* psidt, const double* k0, const doub
 int32_t ora_pcg(int32_t n, const double* psidt, const double* k0, const double* k1,
                 const double* k2, const double* b, double* x, double tol, int32_t maxit,
                 double* relres);
+
+/* ---- learned pressure guess: inputs and solve start (guess.c) ---- */
+int ora_net_inputs(int32_t n, const double* b, const double* diag, const double* p0, double* x,
+                   double* scales);
+int ora_guess_start(int32_t n, const double* psidt, const double* k0, const double* k1,
+                    const double* k2, const double* b, const double* g, double* x0, double* alpha,
+                    double* res_ratio);
 
 /* ---- learned pressure-guess network (conv.c) ---- */
 int32_t ora_conv_nweights(void);

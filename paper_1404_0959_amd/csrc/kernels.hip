@@ -1844,10 +1844,10 @@ __global__ void __launch_bounds__(kBlock) k_dust_flux(Phys ph, const DevState* s
 
 // One Jacobi sweep of the implicit mass-ratio equation
 //   rho^{n+1} Y / dt + (1/V) sum_f G_f^out I4(Y)_f = rho_j^n / dt,
-// diagonal rho^{n+1}/dt + (9/16) div G.
+// diagonal rho^{n+1}/dt + (9/16) div G (returned in diag).
 template <typename T>
 __device__ inline T dust_sweep_cell(const T (&yv)[13], const T (&gpv)[3], const T (&gmv)[3], T rj,
-                                    T r1P, T dt, T inv_V, T rref) {
+                                    T r1P, T dt, T inv_V, T rref, T& diag) {
     T conv = T(0), dG = T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -1858,17 +1858,21 @@ __device__ inline T dust_sweep_cell(const T (&yv)[13], const T (&gpv)[3], const 
     conv *= inv_V;
     dG *= inv_V;
     const T off = conv - T(0.5625) * dG * yv[0];
-    return (rj / dt - off) / ((rref + r1P) / dt + T(0.5625) * dG);
+    diag = (rref + r1P) / dt + T(0.5625) * dG;
+    return (rj / dt - off) / diag;
 }
 
-template <typename T>
+// CHECK (a class's first sweep; the diagonal is the same in every sweep):
+// partials of max(-diagonal), so that a diagonal <= 0 anywhere is flagged.
+template <typename T, bool CHECK>
 __global__ void __launch_bounds__(kBlock) k_dust_sweep(Phys ph, const DevState* st,
                                                        const T* __restrict__ Yin, T* __restrict__ Yout,
                                                        const T* __restrict__ G, const T* __restrict__ rhoj,
-                                                       const T* __restrict__ r1) {
+                                                       const T* __restrict__ r1, double* part) {
     MEMBER(ph)
     const size_t N = ncell(ph);
     const T dt = (T)(st + mem_)->dt, inv_V = (T)ph.inv_V;
+    double v[1] = {-__builtin_inf()};
     FOR_CELLS(ph)
     T yv[13], gpv[3], gmv[3];
     gather13(Yin, c, yv);
@@ -1879,8 +1883,11 @@ __global__ void __launch_bounds__(kBlock) k_dust_sweep(Phys ph, const DevState* 
     }
     const T rj = rhoj[P], r1P = r1[P];
     loads_issued();
-    Yout[P] = dust_sweep_cell(yv, gpv, gmv, rj, r1P, dt, inv_V, (T)(st + mem_)->rho_ref);
+    T dg;
+    Yout[P] = dust_sweep_cell(yv, gpv, gmv, rj, r1P, dt, inv_V, (T)(st + mem_)->rho_ref, dg);
+    if (CHECK) v[0] = fmax(v[0], -(double)dg);
     END_CELLS
+    if (CHECK) block_partials<1, 1u>(v, part);
 }
 
 // Face dust mass fluxes F = G I4(Y), overwriting G on own faces.
@@ -1895,7 +1902,8 @@ __global__ void __launch_bounds__(kBlock) k_dust_faceflux(Phys ph, const T* __re
     END_CELLS
 }
 
-// Conservative finish rho_j^{n+1} = rho_j^n - dt div(F); partial mass sum.
+// Conservative finish rho_j^{n+1} = rho_j^n - dt div(F); partial sums of
+// rho_j^{n+1} (mass; non-finite if any value is) and max(-rho_j^{n+1}).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dust_finish(Phys ph, const DevState* st,
                                                         const T* __restrict__ rhoj,
@@ -1904,7 +1912,7 @@ __global__ void __launch_bounds__(kBlock) k_dust_finish(Phys ph, const DevState*
     MEMBER(ph)
     const size_t N = ncell(ph);
     const T dt = (T)(st + mem_)->dt, inv_V = (T)ph.inv_V;
-    double v[1] = {0.0};
+    double v[2] = {0.0, -__builtin_inf()};
     FOR_CELLS(ph)
     T dF = T(0);
 #pragma unroll
@@ -1912,8 +1920,9 @@ __global__ void __launch_bounds__(kBlock) k_dust_finish(Phys ph, const DevState*
     const T out = rhoj[P] - dt * dF * inv_V;
     rhoj1[P] = out;
     v[0] += (double)out;
+    v[1] = fmax(v[1], -(double)out);
     END_CELLS
-    block_partials<1, 0u>(v, partials);
+    block_partials<2, 2u>(v, partials);
 }
 
 // ---------------------------------------------------------------- statistics
@@ -1983,11 +1992,14 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(const double* part, uns
 
 // One block per member at the end of a step: mass budget, divergence flags
 // and the dust class masses from the partials of the last corrector and of
-// the dust finish.
+// the dust finish, and the dust flags: 64 some rho_j < 0, 128 a non-finite
+// rho_j (the sum is then non-finite), 256 the implicit diagonal <= 0 in some
+// cell (from the first sweep's maxima of -diagonal).
 __global__ void __launch_bounds__(kBlock) k_step_finish(Phys ph, DevState* st,
                                                         const double* part_mass, unsigned nb_mass,
                                                         const double* part_dust, int ncls,
-                                                        unsigned nb_dust, size_t cls_stride) {
+                                                        unsigned nb_dust, const double* part_diag,
+                                                        unsigned nb_diag, size_t cls_stride) {
     const int m = blockIdx.x;
     DevState* sm = st + m;
     double v[3];
@@ -2000,9 +2012,16 @@ __global__ void __launch_bounds__(kBlock) k_step_finish(Phys ph, DevState* st,
         if (!(-v[2] > 0.0)) sm->flags |= 4;
     }
     for (int c = 0; c < ncls; ++c) {
-        double mm[1];
-        reduce_member<1, 0u>(part_dust + (size_t)c * cls_stride, nb_dust, ph.batch, m, mm);
-        if (flat_tid() == 0) sm->mass_p[c] = mm[0] * ph.V;
+        // columns nb_dust apart: sum rho_j, max(-rho_j)
+        double mm[2], dg[1];
+        reduce_member<2, 2u>(part_dust + (size_t)(2 * c) * cls_stride, nb_dust, ph.batch, m, mm);
+        reduce_member<1, 1u>(part_diag + (size_t)c * cls_stride, nb_diag, ph.batch, m, dg);
+        if (flat_tid() == 0) {
+            sm->mass_p[c] = mm[0] * ph.V;
+            if (!isfinite(mm[0])) sm->flags |= 128;
+            else if (mm[1] > 0.0) sm->flags |= 64;
+            if (!(dg[0] < 0.0)) sm->flags |= 256;
+        }
     }
 }
 
@@ -2579,10 +2598,12 @@ struct TiledDustFlux : TiledBase<T> {
     }
 };
 
-template <typename T>
+template <typename T, bool CHECK>
 struct TiledDustSweep : TiledBase<T> {
     static constexpr int NS = 1;          // Y_in
     static constexpr bool FACES = true;   // G
+    static constexpr int NR = CHECK ? 1 : 0;   // max(-diagonal), as k_dust_sweep
+    static constexpr unsigned MASK = 1u;
     const T* sf[1];
     const T *rhoj, *r1;
     T* Yout;
@@ -2594,9 +2615,12 @@ struct TiledDustSweep : TiledBase<T> {
         rref = (T)d->rho_ref;
     }
     __device__ Pts load(size_t P) const { return {stream_ld(rhoj + P), stream_ld(r1 + P)}; }
+    __device__ void init(double* acc) const { acc[0] = -__builtin_inf(); }
     __device__ void cell(size_t P, const T (&v)[1][13], const T (&fp)[3], const T (&fm)[3],
-                         const Pts& p, double*) const {
-        stream_st(Yout + P, dust_sweep_cell(v[0], fp, fm, p.rj, p.r1, dt, inv_V, rref));
+                         const Pts& p, double* acc) const {
+        T dg;
+        stream_st(Yout + P, dust_sweep_cell(v[0], fp, fm, p.rj, p.r1, dt, inv_V, rref, dg));
+        if (CHECK) acc[0] = fmax(acc[0], -(double)dg);
     }
 };
 
@@ -2609,7 +2633,8 @@ template <typename T>
 struct TiledDustFinish : TiledBase<T> {
     static constexpr int NS = 1;          // Y
     static constexpr bool FACES = true;   // G
-    static constexpr int NR = 1;
+    static constexpr int NR = 2;          // sum rho_j, max(-rho_j), as k_dust_finish
+    static constexpr unsigned MASK = 2u;
     const T* sf[1];
     const T* rhoj;
     T* rhoj1;
@@ -2620,6 +2645,10 @@ struct TiledDustFinish : TiledBase<T> {
         inv_V = (T)ph.inv_V;
     }
     __device__ Pts load(size_t P) const { return {stream_ld(rhoj + P)}; }
+    __device__ void init(double* acc) const {
+        acc[0] = 0.0;
+        acc[1] = -__builtin_inf();
+    }
     __device__ void cell(size_t P, const T (&v)[1][13], const T (&fp)[3], const T (&fm)[3],
                          const Pts& p, double* acc) const {
         T dF = T(0);
@@ -2628,6 +2657,7 @@ struct TiledDustFinish : TiledBase<T> {
         const T out = p.rj - dt * dF * inv_V;
         stream_st(rhoj1 + P, out);
         acc[0] += (double)out;
+        acc[1] = fmax(acc[1], -(double)out);
     }
 };
 
@@ -3106,21 +3136,29 @@ void Ops<T>::dust_flux(const Launch& L, const Launch& TL, hipStream_t s, const P
     }
     LAUNCH(k_dust_flux<T>, L, s, ph, st, cls, phi, r1, acc, G, rhoj, rn, Y);
 }
+template <typename T, bool CHECK>
+static unsigned dust_sweep_tiled(const Launch& TL, hipStream_t s, const Phys& ph,
+                                 const DevState* st, const T* Yin, T* Yout, const T* G,
+                                 const T* rhoj, const T* r1, double* part_diag) {
+    TiledDustSweep<T, CHECK> k{};
+    k.sf[0] = Yin;
+    k.face = G;
+    k.rhoj = rhoj;
+    k.r1 = r1;
+    k.Yout = Yout;
+    k.part = part_diag;
+    return tiled_launch<T>(TL, s, ph, st, k);
+}
 template <typename T>
-void Ops<T>::dust_sweep(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
-                        const DevState* st, const T* Yin, T* Yout, const T* G, const T* rhoj,
-                        const T* r1) {
-    if (TL.nblocks) {
-        TiledDustSweep<T> k{};
-        k.sf[0] = Yin;
-        k.face = G;
-        k.rhoj = rhoj;
-        k.r1 = r1;
-        k.Yout = Yout;
-        tiled_launch<T>(TL, s, ph, st, k);
-        return;
-    }
-    LAUNCH(k_dust_sweep<T>, L, s, ph, st, Yin, Yout, G, rhoj, r1);
+unsigned Ops<T>::dust_sweep(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                            const DevState* st, const T* Yin, T* Yout, const T* G, const T* rhoj,
+                            const T* r1, double* part_diag) {
+    if (TL.nblocks)
+        return part_diag ? dust_sweep_tiled<T, true>(TL, s, ph, st, Yin, Yout, G, rhoj, r1, part_diag)
+                         : dust_sweep_tiled<T, false>(TL, s, ph, st, Yin, Yout, G, rhoj, r1, nullptr);
+    if (part_diag) LAUNCH((k_dust_sweep<T, true>), L, s, ph, st, Yin, Yout, G, rhoj, r1, part_diag);
+    else LAUNCH((k_dust_sweep<T, false>), L, s, ph, st, Yin, Yout, G, rhoj, r1, nullptr);
+    return L.nblocks;
 }
 template <typename T>
 void Ops<T>::dust_faceflux(const Launch& L, hipStream_t s, const Phys& ph, const T* Y, T* G) {
@@ -3195,9 +3233,9 @@ void sum_partials(hipStream_t s, const double* part, unsigned nb, double* dst) {
 }
 void step_finish(hipStream_t s, const Phys& ph, DevState* st, const double* part_mass,
                  unsigned nb_mass, const double* part_dust, int ncls, unsigned nb_dust,
-                 size_t cls_stride) {
+                 const double* part_diag, unsigned nb_diag, size_t cls_stride) {
     hipLaunchKernelGGL(k_step_finish, dim3(ph.batch), dim3(64, 4), 0, s, ph, st, part_mass,
-                       nb_mass, part_dust, ncls, nb_dust, cls_stride);
+                       nb_mass, part_dust, ncls, nb_dust, part_diag, nb_diag, cls_stride);
 }
 void commit(hipStream_t s, DevState* st, int batch) {
     hipLaunchKernelGGL(k_commit, dim3((batch + 63) / 64), dim3(64), 0, s, st, batch);

@@ -62,8 +62,13 @@ enum PartSlot {
     PS_MASS = PS_CG + 2 * kCgCols,   // 3 columns: sum r, sum |u|^2, max(-rho)
     PS_CFL = PS_MASS + 3,            // 1 column: Courant maxima (k_cfl); must follow PS_MASS
     PS_STAT = PS_CFL + 1,            // 4 columns: statistics
-    PS_DUST = PS_STAT + 4,           // kMaxClasses columns: dust class masses
-    PS_COLUMNS = PS_DUST + kMaxClasses
+    // 2 kMaxClasses columns: class c's dust finish writes, from PS_DUST + 2c
+    // on, columns of nb partials each: sum rho_j, then max(-rho_j)
+    PS_DUST = PS_STAT + 4,
+    // kMaxClasses columns: max(-diagonal) of class c's implicit equation, from
+    // its first sweep
+    PS_DDIAG = PS_DUST + 2 * kMaxClasses,
+    PS_COLUMNS = PS_DDIAG + kMaxClasses
 };
 
 // Operands of CG iteration k.  Reads r_{k-1}, p_{k-1}, q_{k-1} (rin, pold,
@@ -162,14 +167,18 @@ struct Ops {
     static void dust_flux(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                           const DevState* st, int cls, const T* phi, const T* r1, const T* acc,
                           T* G, const T* rhoj, const T* rn, T* Y);
-    static void dust_sweep(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
-                           const DevState* st, const T* Yin, T* Yout, const T* G,
-                           const T* rhoj, const T* r1);
+    // part_diag non-null (the class's first sweep): partials max(-diagonal)
+    // of the implicit equation; returns the launch's block count
+    static unsigned dust_sweep(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                               const DevState* st, const T* Yin, T* Yout, const T* G,
+                               const T* rhoj, const T* r1, double* part_diag);
     static void dust_faceflux(const Launch& L, hipStream_t s, const Phys& ph, const T* Y, T* G);
+    // partials: two columns of L.nblocks from part on, sum rho_j and max(-rho_j)
     static void dust_finish(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                             const T* rhoj, const T* F, T* rhoj1, double* part);
     // dust_faceflux and dust_finish in one tiled pass (TL.nblocks > 0), F not
-    // stored; returns the number of partials written
+    // stored; returns the number of partials written per column (two columns,
+    // as dust_finish)
     static unsigned dust_finish_fused(const Launch& TL, hipStream_t s, const Phys& ph,
                                       const DevState* st, const T* Y, const T* G,
                                       const T* rhoj, T* rhoj1, double* part);
@@ -205,9 +214,11 @@ void finalize_sums(hipStream_t s, const double* part, unsigned nbt, int batch, i
 void sum_partials(hipStream_t s, const double* part, unsigned nb, double* dst);
 // Per member: end-of-step mass budget and flags.
 // nb_mass: partials of the last corrector update; nb_dust: of the dust finish
+// (class c's two columns from part_dust + 2 c cls_stride); nb_diag: of the
+// first dust sweep (class c's column at part_diag + c cls_stride)
 void step_finish(hipStream_t s, const Phys& ph, DevState* st, const double* part_mass,
                  unsigned nb_mass, const double* part_dust, int ncls, unsigned nb_dust,
-                 size_t cls_stride);
+                 const double* part_diag, unsigned nb_diag, size_t cls_stride);
 // Per member: t += dt, dt_prev = dt (the step is accepted); fold the step
 // record into the accumulators.
 void commit(hipStream_t s, DevState* st, int batch);

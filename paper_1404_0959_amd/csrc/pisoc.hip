@@ -65,7 +65,9 @@ struct Layout {
     size_t rn, rk, aP, divu, pn, w, p0, r, r2, x, diag, pp0, pp1, pp2, q, q2, Y0, Y1;
     size_t u3[3], phin, phik, src, hbya, phiH, acc, G;
     size_t rhop, rhop1;
-    size_t snap;   // 4 FP64 fields when capturing
+    // FP64 fields when capturing: b, diag, p0, p', w = rho/a_P (snapshot slots
+    // 0-4), u* (5-7), and with the learned guess g and the solve start x0 (8, 9)
+    size_t snap;
     size_t b64, x64a, x64b, xf;  // FP64 refinement fields, FP32 solution copy (FP32 storage only)
     size_t wpk, nx4, na, nb, ny, bsave;  // learned guess: packed weights, activations
     size_t total;
@@ -200,7 +202,8 @@ Layout make_layout(const pisoc_params* p, int batch) {
     for (size_t* o : three) *o = take(3 * es * N);
     L.rhop = take(es * N * (size_t)std::max(p->n_classes, 1));
     L.rhop1 = take(es * N * (size_t)std::max(p->n_classes, 1));
-    L.snap = p->capture ? take(4 * sizeof(double) * N) : 0;
+    L.snap = p->capture ? take((p->guess == PISOC_GUESS_LEARNED ? 10 : 8) * sizeof(double) * N)
+                        : 0;
     if (p->guess == PISOC_GUESS_LEARNED) {
         L.wpk = take(net_packed_bytes());
         L.nx4 = take(4 * 2 * N);
@@ -576,6 +579,9 @@ void enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
               [&] { O::mom_sweep(L, ctx->TL, s, ph, st, uin, uout, S.phin, S.aP, S.src, S.pn); });
         uin = uout;
     }
+    if (S.snap)   // the predictor's output u*
+        for (int d = 0; d < 3; ++d)
+            O::cast_out(s, uin + d * ctx->NT(), S.snap + (5 + d) * ctx->NT(), ctx->NT(), 0.0);
 }
 
 template <typename T>
@@ -593,6 +599,7 @@ void enqueue_corr_setup(pisoc_ctx* ctx, StepPtrs<T>& S, int corr, bool guess) {
     timed(ctx, KC_HBYA, 16, -1,
           [&] { O::hbya(L, ctx->TL, s, ph, ctx->st, ucur, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0); });
     const bool cap = S.snap && corr == 0;
+    if (cap) O::cast_out(s, S.w, S.snap + 4 * N, N, 0.0);   // the operator's w = rho/a_P
     timed(ctx, KC_CORR_RHS, f32 ? 14 : 12, -1, [&] {
         ctx->nb_start = O::corr_rhs(L, ctx->TL, s, ph, ctx->st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH,
                                     S.r, S.dg, ctx->part(PS_U), cap ? S.snap : nullptr,
@@ -602,6 +609,16 @@ void enqueue_corr_setup(pisoc_ctx* ctx, StepPtrs<T>& S, int corr, bool guess) {
     if (guess) {
         learned_guess<T>(ctx, S.r, S.x, S.dg, S.w, S.p0, S.pp0, S.q);
         ctx->nb_start = L.nblocks;   // the guess rewrites the start's partials
+        if (cap) {
+            // the network's guess g (left in pp0) and the solve's start x0 (x, or
+            // x64 in FP32 storage, where x holds the zero inner correction)
+            O::cast_out(s, S.pp0, S.snap + 8 * N, N, 0.0);
+            if (f32)
+                (void)hipMemcpyAsync(S.snap + 9 * N, S.x64a, N * sizeof(double),
+                                     hipMemcpyDeviceToDevice, s);
+            else
+                O::cast_out(s, S.x, S.snap + 9 * N, N, 0.0);
+        }
     }
 }
 
@@ -642,6 +659,7 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
     using O = Ops<T>;
     const pisoc_params& p = ctx->prm;
     unsigned nb_dust = ctx->L.nblocks;   // partials of the dust finish
+    unsigned nb_diag = ctx->L.nblocks;   // ... of the first dust sweep (its diagonal check)
     const Phys& ph = ctx->ph;
     const Launch& L = ctx->L;
     hipStream_t s = ctx->stream;
@@ -658,27 +676,32 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
             T* yin = S.Ya;
             T* yout = S.Yb;
             for (int i = 0; i < p.n_dust_sweeps; ++i) {
-                timed(ctx, KC_DUST_SWEEP, 7, -1,
-                      [&] { O::dust_sweep(L, ctx->TL, s, ph, st, yin, yout, S.G, S.rj + c * N, S.rk); });
+                // the first sweep also checks the implicit diagonal (the same in every sweep)
+                double* chk = i == 0 ? ctx->part(PS_DDIAG + c) : nullptr;
+                timed(ctx, KC_DUST_SWEEP, 7, -1, [&] {
+                    const unsigned nb =
+                        O::dust_sweep(L, ctx->TL, s, ph, st, yin, yout, S.G, S.rj + c * N, S.rk, chk);
+                    if (chk) nb_diag = nb;
+                });
                 std::swap(yin, yout);
             }
             if (ctx->TL.nblocks) {
                 // face fluxes and finish in one tiled pass (words: Y, G, rho_j read, rho_j' written)
                 timed(ctx, KC_DUST_FINISH, 6, -1, [&] {
                     nb_dust = O::dust_finish_fused(ctx->TL, s, ph, st, yin, S.G, S.rj + c * N,
-                                                   S.rj1 + c * N, ctx->part(PS_DUST + c));
+                                                   S.rj1 + c * N, ctx->part(PS_DUST + 2 * c));
                 });
             } else {
                 timed(ctx, KC_DUST_FACEFLUX, 7, -1, [&] { O::dust_faceflux(L, s, ph, yin, S.G); });
                 timed(ctx, KC_DUST_FINISH, 5, -1, [&] {
                     O::dust_finish(L, s, ph, st, S.rj + c * N, S.G, S.rj1 + c * N,
-                                   ctx->part(PS_DUST + c));
+                                   ctx->part(PS_DUST + 2 * c));
                 });
             }
         }
     }
     step_finish(s, ph, st, ctx->part(PS_MASS), ctx->nb_mass, ctx->part(PS_DUST), p.n_classes,
-                nb_dust, ctx->lay.max_blocks);
+                nb_dust, ctx->part(PS_DDIAG), nb_diag, ctx->lay.max_blocks);
 }
 
 // Iterations past a solve's predicted count that an eager FP32 first round
@@ -722,7 +745,7 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
                                           kSpecMargin, p.p_maxit)
                            : ctx->caps[corr];
     if ((*err = run_pcg<float>(ctx, cg_vecs(S), true, cap0, false, nullptr, !guess, ctx->nb_start,
-                               eager ? cap0 : 0)) != PISOC_OK)
+                               cap0)) != PISOC_OK)
         return;
     record_solve(s, ctx->st, B, corr, /*round=*/1, /*add=*/1, /*fin=*/0);
     bool waited = false;   // the host has seen the state since the first round
@@ -776,7 +799,7 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
         // the inner correction of this round starts from zero (not written)
         const int pairs = eager ? std::max(2, ctx->pred_later) : ctx->cap_later;
         if ((*err = run_pcg<float>(ctx, cg_vecs(S), false, pairs, eager,
-                                   &most, true, nb_ref)) != PISOC_OK)
+                                   &most, true, nb_ref, eager ? 0 : pairs)) != PISOC_OK)
             return;
         if (eager) ctx->pred_later = most;
         record_solve(s, ctx->st, B, corr, round + 1, /*add=*/1, /*fin=*/0);
@@ -883,8 +906,10 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
             int most = 0;
             const int pairs =
                 eager ? (ctx->pred_first[corr] > 0 ? ctx->pred_first[corr] : 8) : ctx->caps[corr];
+            // a captured solve stops at its cap at the latest: its last launch
+            // brings x up to date with the residual it reports
             err = run_pcg<T>(ctx, cg_vecs(S), true, pairs, eager, &most,
-                             !guess, ctx->nb_start);
+                             !guess, ctx->nb_start, eager ? 0 : pairs);
             if (eager) ctx->pred_first[corr] = most;
             record_solve(s, ctx->st, ctx->batch, corr, /*round=*/0, /*add=*/1, /*fin=*/1);
         }
@@ -931,7 +956,8 @@ void fill_info(const pisoc_ctx* ctx, const DevState& h, bool committed, pisoc_st
 }
 
 bool member_bad(const pisoc_ctx* ctx, const DevState& h) {
-    bool bad = (h.flags & (PISOC_FLAG_NONFINITE | PISOC_FLAG_RHO_NONPOS)) != 0;
+    bool bad = (h.flags & (PISOC_FLAG_NONFINITE | PISOC_FLAG_RHO_NONPOS |
+                           PISOC_FLAG_DUST_NONFINITE)) != 0;
     for (int c = 0; c < ctx->prm.n_classes; ++c)
         if (!std::isfinite(h.mass_p[c])) bad = true;
     return bad;
@@ -939,6 +965,7 @@ bool member_bad(const pisoc_ctx* ctx, const DevState& h) {
 
 pisoc_status flag_status(int flags) {
     if (flags & PISOC_FLAG_PCG_MAXIT) return PISOC_WARN_NOT_CONVERGED;
+    if (flags & (PISOC_FLAG_DUST_NEG | PISOC_FLAG_DUST_DIAG)) return PISOC_WARN_DUST;
     if (flags & PISOC_FLAG_GUESS_FALLBACK) return PISOC_WARN_GUESS_FALLBACK;
     return PISOC_OK;
 }
@@ -981,7 +1008,8 @@ pisoc_status eager_step(pisoc_ctx* ctx, pisoc_step_info* info) {
         worst = combine_status(worst, flag_status(h.flags));
     }
     if (bad) {
-        ctx->err = "step diverged (non-finite field or non-positive density); state kept";
+        ctx->err = "step diverged (non-finite field, non-positive density or non-finite dust "
+                   "density); state kept";
         if (info)
             for (int m = 0; m < ctx->batch; ++m) {
                 fill_info(ctx, ctx->hst[m], false, info + m);
@@ -1184,16 +1212,31 @@ pisoc_status member_fields(pisoc_ctx* ctx, int m, uint32_t which, double* const*
             case PISOC_FIELD_PSOLVE_B:
             case PISOC_FIELD_PSOLVE_DIAG:
             case PISOC_FIELD_P_PREV:
-            case PISOC_FIELD_PSOLVE_X: {
+            case PISOC_FIELD_PSOLVE_X:
+            case PISOC_FIELD_PSOLVE_W:
+            case PISOC_FIELD_USTAR:
+            case PISOC_FIELD_GUESS:
+            case PISOC_FIELD_GUESS_X0: {
                 if (!snap) {
                     ctx->err = "captured pressure system requested without params.capture";
                     return PISOC_ERR_INVALID;
                 }
+                const bool gsel = mk == PISOC_FIELD_GUESS || mk == PISOC_FIELD_GUESS_X0;
+                if (gsel && ctx->prm.guess != PISOC_GUESS_LEARNED) {
+                    ctx->err = "captured guess requested without the learned guess";
+                    return PISOC_ERR_INVALID;
+                }
                 const int idx = mk == PISOC_FIELD_PSOLVE_B ? 0
                                 : mk == PISOC_FIELD_PSOLVE_DIAG ? 1
-                                : mk == PISOC_FIELD_P_PREV ? 2 : 3;
-                HIP_TRY(ctx, hipMemcpyAsync(dst, snap + idx * NT + off, N * sizeof(double),
-                                            hipMemcpyDeviceToDevice, s));
+                                : mk == PISOC_FIELD_P_PREV ? 2
+                                : mk == PISOC_FIELD_PSOLVE_X ? 3
+                                : mk == PISOC_FIELD_PSOLVE_W ? 4
+                                : mk == PISOC_FIELD_USTAR ? 5
+                                : mk == PISOC_FIELD_GUESS ? 8 : 9;
+                const int comps = mk == PISOC_FIELD_USTAR ? 3 : 1;
+                for (int d = 0; d < comps; ++d)
+                    HIP_TRY(ctx, hipMemcpyAsync(dst + d * N, snap + (idx + d) * NT + off,
+                                                N * sizeof(double), hipMemcpyDeviceToDevice, s));
                 break;
             }
             default: ctx->err = "unknown field bit"; return PISOC_ERR_INVALID;
@@ -1350,7 +1393,8 @@ void enqueue_probe(pisoc_ctx* ctx) {
     // against 6-8 momentum sweeps)
     set_tol(s, st, ctx->batch, 0.0);
     (void)run_pcg<T>(ctx, cg_vecs(S), true, kProbeCgIters, false, nullptr, true, nb0);
-    if (ctx->prm.n_classes > 0) O::dust_sweep(L, ctx->TL, s, ph, st, S.Ya, S.Yb, S.G, S.rj, S.rk);
+    if (ctx->prm.n_classes > 0)
+        (void)O::dust_sweep(L, ctx->TL, s, ph, st, S.Ya, S.Yb, S.G, S.rj, S.rk, nullptr);
 }
 
 // The CG kernel's tile launch with z-chunks of cgz planes (0: the default).
@@ -1648,6 +1692,7 @@ const char* pisoc_status_string(pisoc_status st) {
         case PISOC_OK: return "ok";
         case PISOC_WARN_NOT_CONVERGED: return "pressure solve did not converge";
         case PISOC_WARN_GUESS_FALLBACK: return "learned guess rejected";
+        case PISOC_WARN_DUST: return "dust density negative or dust diagonal non-positive";
         case PISOC_ERR_INVALID: return "invalid argument";
         case PISOC_ERR_HIP: return "HIP error";
         case PISOC_ERR_DIVERGED: return "diverged";
@@ -1828,7 +1873,13 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
                     return s;
                 }
                 worst = combine_status(worst, s);
-                for (int j = 0; j < ctx->batch; ++j) rec[e->members[c][j]] = ci[j];
+                // the call's records: each member's last step, flags of all its steps
+                for (int j = 0; j < ctx->batch; ++j) {
+                    pisoc_step_info& r = rec[e->members[c][j]];
+                    const int32_t before = r.flags;
+                    r = ci[j];
+                    r.flags |= before;
+                }
                 // iterations for the caps of the captured step
                 int first[PISOC_MAX_CORR] = {0, 0, 0, 0};
                 int later = 0, rounds = 1;
@@ -1843,6 +1894,10 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
                 set_caps(ctx, first, later, rounds);
             }
             e->steps += 1;
+            // the eager step rotated the buffers: graphs already built stay valid
+            // for the other parity (their kernel arguments are the rotation's
+            // pointers), so the next replay takes exec[c][parity ^ 1]
+            if (e->built) e->parity ^= 1;
         }
         if (mode == PISOC_ENS_EAGER) {
             if (h_info) std::copy(rec.begin(), rec.end(), h_info);
@@ -1857,7 +1912,11 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
             return worst;
         }
         pisoc_status st = build_graphs(e);
-        if (st != PISOC_OK) return st;
+        if (st != PISOC_OK) {
+            // the eager steps of this call stand; their records go out with the error
+            if (h_info) std::copy(rec.begin(), rec.end(), h_info);
+            return st;
+        }
     }
     if (n_steps > 0) {
         // each class's graph runs on the class stream, after the work already
@@ -1892,10 +1951,13 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
                     skipped |= ctx->audit.use[q] ? 0 : PISOC_FLAG_GUESS_SKIPPED;
             for (int j = 0; j < ctx->batch; ++j) {
                 const DevState& h = ctx->hst[j];
-                fill_info(ctx, h, true, &rec[e->members[c][j]]);
-                rec[e->members[c][j]].flags |= h.flags_acc | skipped;
+                pisoc_step_info& r = rec[e->members[c][j]];
+                const int32_t before = r.flags;   // the call's leading eager steps
+                fill_info(ctx, h, true, &r);
+                r.flags |= h.flags_acc | skipped | before;
                 worst = combine_status(worst, flag_status(h.flags_acc));
-                if (member_bad(ctx, h) || (h.flags_acc & (PISOC_FLAG_NONFINITE | PISOC_FLAG_RHO_NONPOS)))
+                if (member_bad(ctx, h) ||
+                    (h.flags_acc & (PISOC_FLAG_NONFINITE | PISOC_FLAG_RHO_NONPOS | PISOC_FLAG_DUST_NONFINITE)))
                     bad = true;
                 for (int q = 0; q < ctx->prm.n_corr; ++q) first[q] = std::max(first[q], h.it_first_max[q]);
                 for (int q = 0; q < ctx->prm.n_corr; ++q) later = std::max(later, h.it_later_max[q]);
@@ -1937,7 +1999,8 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
             return PISOC_ERR_INVALID;
         }
         if (bad) {
-            e->err = "a member diverged (non-finite field or non-positive density)";
+            e->err = "a member diverged (non-finite field, non-positive density or non-finite "
+                     "dust density)";
             if (h_info) std::copy(rec.begin(), rec.end(), h_info);
             return PISOC_ERR_DIVERGED;
         }
@@ -2083,23 +2146,18 @@ pisoc_status pisoc_helm_apply(int32_t n, const double* d_psidt, const double* d_
     return hipGetLastError() == hipSuccess ? PISOC_OK : PISOC_ERR_HIP;
 }
 
-pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_w,
-                              const double* d_b, double* d_x, double tol, int32_t maxit,
-                              void* d_workspace, size_t ws_bytes, void* hip_stream,
-                              int32_t* iters, double* relres) {
-    if (n < PISOC_MIN_N || n > PISOC_MAX_N || !d_psidt || !d_w || !d_b || !d_x ||
-        !(tol > 0.0) || !(tol < 1.0) || maxit < 1)
-        return PISOC_ERR_INVALID;
-    const Layout lay = helm_layout(n);
-    if (!d_workspace || ws_bytes < lay.total ||
-        (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
-        return PISOC_ERR_WORKSPACE;
+// The solve of pisoc_helm_solve on the workspace ws (laid out as lay), with
+// hst a host DevState the state is read back into.
+static pisoc_status helm_solve_on(int32_t n, const double* d_psidt, const double* d_w,
+                                  const double* d_b, double* d_x, double tol, int32_t maxit,
+                                  char* ws, const Layout& lay, DevState* hst, hipStream_t stream,
+                                  int32_t* iters, double* relres) {
     pisoc_ctx ctx{};
     ctx.prm = plain_params(n);
     ctx.prm.p_maxit = maxit;
     ctx.batch = 1;
-    ctx.stream = reinterpret_cast<hipStream_t>(hip_stream);
-    ctx.ws = reinterpret_cast<char*>(d_workspace);
+    ctx.stream = stream;
+    ctx.ws = ws;
     ctx.lay = lay;
     ctx.L = make_launch(n, 1);
     ctx.TL = make_tiled_launch(n, 1);
@@ -2108,11 +2166,7 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
     ctx.es = sizeof(double);
     ctx.st = reinterpret_cast<DevState*>(ctx.ws + lay.state);
     ctx.partials = reinterpret_cast<double*>(ctx.ws + lay.partials);
-    if (hipHostMalloc(reinterpret_cast<void**>(&ctx.hst), sizeof(DevState), hipHostMallocDefault) !=
-        hipSuccess) {
-        ctx.hst = nullptr;
-        return PISOC_ERR_HIP;
-    }
+    ctx.hst = hst;
     DevState init{};
     init.pcg.tol2 = tol * tol;
     init.pcg.tol_final = tol * tol;
@@ -2147,8 +2201,30 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
             if (!g.converged) st = PISOC_WARN_NOT_CONVERGED;
         }
     }
-    (void)hipHostFree(ctx.hst);
+    // the host copies of the state are the caller's; the context must not free them
     ctx.hst = nullptr;
+    return st;
+}
+
+pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_w,
+                              const double* d_b, double* d_x, double tol, int32_t maxit,
+                              void* d_workspace, size_t ws_bytes, void* hip_stream,
+                              int32_t* iters, double* relres) {
+    if (n < PISOC_MIN_N || n > PISOC_MAX_N || !d_psidt || !d_w || !d_b || !d_x ||
+        !(tol > 0.0) || !(tol < 1.0) || maxit < 1)
+        return PISOC_ERR_INVALID;
+    const Layout lay = helm_layout(n);
+    if (!d_workspace || ws_bytes < lay.total ||
+        (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
+        return PISOC_ERR_WORKSPACE;
+    DevState* hst = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&hst), sizeof(DevState), hipHostMallocDefault) !=
+        hipSuccess)
+        return PISOC_ERR_HIP;
+    const pisoc_status st =
+        helm_solve_on(n, d_psidt, d_w, d_b, d_x, tol, maxit, reinterpret_cast<char*>(d_workspace),
+                      lay, hst, reinterpret_cast<hipStream_t>(hip_stream), iters, relres);
+    (void)hipHostFree(hst);
     return st;
 }
 

@@ -16,15 +16,17 @@ LIB_PATH = os.path.join(HERE, "libpisoc.so")
 MAX_CLASSES = 8
 MAX_CORR = 4
 
-OK, WARN_NOT_CONVERGED, WARN_GUESS_FALLBACK = 0, 1, 2
+OK, WARN_NOT_CONVERGED, WARN_GUESS_FALLBACK, WARN_DUST = 0, 1, 2, 3
 ERR_INVALID, ERR_HIP, ERR_DIVERGED, ERR_WORKSPACE = -1, -2, -3, -4
 FP64, FP32_REFINED = 0, 1
 GUESS_ZERO, GUESS_LEARNED = 0, 1
 FLAG_PCG_MAXIT, FLAG_NONFINITE, FLAG_RHO_NONPOS, FLAG_GUESS_FALLBACK, FLAG_BAD_DT = 1, 2, 4, 8, 16
 FLAG_GUESS_SKIPPED = 32
+FLAG_DUST_NEG, FLAG_DUST_NONFINITE, FLAG_DUST_DIAG = 64, 128, 256
 
 FIELD_RHO, FIELD_U, FIELD_PHI, FIELD_RHO_P, FIELD_P = 1, 2, 4, 8, 16
 FIELD_PSOLVE_B, FIELD_PSOLVE_X, FIELD_P_PREV, FIELD_PSOLVE_DIAG = 32, 64, 128, 256
+FIELD_USTAR, FIELD_GUESS, FIELD_GUESS_X0, FIELD_PSOLVE_W = 512, 1024, 2048, 4096
 
 EXPORTED = [
     "pisoc_workspace_bytes", "pisoc_init", "pisoc_step", "pisoc_fields", "pisoc_get_stats",
@@ -281,7 +283,9 @@ class Solver:
         shapes = {FIELD_RHO: (n, n, n), FIELD_U: (3, n, n, n), FIELD_PHI: (3, n, n, n),
                   FIELD_RHO_P: (max(self.K, 1), n, n, n), FIELD_P: (n, n, n),
                   FIELD_PSOLVE_B: (n, n, n), FIELD_PSOLVE_X: (n, n, n),
-                  FIELD_P_PREV: (n, n, n), FIELD_PSOLVE_DIAG: (n, n, n)}
+                  FIELD_P_PREV: (n, n, n), FIELD_PSOLVE_DIAG: (n, n, n),
+                  FIELD_USTAR: (3, n, n, n), FIELD_GUESS: (n, n, n), FIELD_GUESS_X0: (n, n, n),
+                  FIELD_PSOLVE_W: (n, n, n)}
         bits = [b for b in sorted(shapes) if which & b]
         outs = [torch.empty(shapes[b], dtype=torch.float64, device=self.device) for b in bits]
         arr = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
@@ -419,7 +423,11 @@ class Ensemble:
         torch = self.torch
         n = self.ns[m]
         shapes = {FIELD_RHO: (n, n, n), FIELD_U: (3, n, n, n), FIELD_PHI: (3, n, n, n),
-                  FIELD_RHO_P: (max(self.K, 1), n, n, n), FIELD_P: (n, n, n)}
+                  FIELD_RHO_P: (max(self.K, 1), n, n, n), FIELD_P: (n, n, n),
+                  FIELD_PSOLVE_B: (n, n, n), FIELD_PSOLVE_X: (n, n, n),
+                  FIELD_P_PREV: (n, n, n), FIELD_PSOLVE_DIAG: (n, n, n),
+                  FIELD_USTAR: (3, n, n, n), FIELD_GUESS: (n, n, n), FIELD_GUESS_X0: (n, n, n),
+                  FIELD_PSOLVE_W: (n, n, n)}
         bits = [b for b in sorted(shapes) if which & b]
         outs = [torch.empty(shapes[b], dtype=torch.float64, device=self.device) for b in bits]
         arr = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
@@ -544,3 +552,4 @@ def helm_solve(psidt, w, b, x0=None, tol=1e-10, maxit=1000, stream=None):
     if st < 0:
         raise PisocError(st, "pisoc_helm_solve")
     return x, it.value, rel.value, st
+

@@ -97,8 +97,10 @@ def test_workspace_checked_before_gpu_work(lib):
 
 
 def test_status_strings(lib):
-    for st in (0, 1, 2, -1, -2, -3, -4):
+    for st in (0, 1, 2, 3, -1, -2, -3, -4):
         assert lib.pisoc_status_string(st)
+        assert lib.pisoc_status_string(st) != b"unknown status"
+
 
 
 # C structs of the header and their ctypes mirrors in the binding

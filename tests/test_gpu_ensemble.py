@@ -54,10 +54,11 @@ def test_eager_members_equal_single_runs(P):
     assert [c["members"] for c in ens.classes()] == [2, 1]
     for step in range(3):
         st, infos = ens.step(1, mode=P.ENS_EAGER)
-        assert st == P.OK
+        assert st in (P.OK, P.WARN_DUST)
         for m, s in enumerate(singles):
             st1, (i1,) = s.step(1)
-            assert st1 == P.OK
+            assert st1 in (P.OK, P.WARN_DUST)
+            assert infos[m]["flags"] == i1["flags"], (step, m)
             assert infos[m]["pcg_iters"] == i1["pcg_iters"], (step, m)
             assert infos[m]["dt"] == i1["dt"] and infos[m]["t"] == i1["t"]
             assert infos[m]["mass_gas"] == i1["mass_gas"]
@@ -81,7 +82,7 @@ def test_member_matches_oracle(P, ora):
     o = ora.Oracle.from_case(cs[1], **kw)
     st, infos = ens.step(2, mode=P.ENS_EAGER)
     st_o, info_o = o.step(2)
-    assert st == st_o == 0
+    assert st == st_o and st in (P.OK, P.WARN_DUST)
     assert infos[1]["pcg_iters"] == info_o[-1]["pcg_iters"]
 
     class View:
@@ -98,7 +99,7 @@ def test_graph_reproduces_eager_fp64(P):
     for _ in range(4):
         sa, ia = a.step(1, mode=P.ENS_EAGER)
     sb, ib = b.step(4, mode=P.ENS_GRAPH)
-    assert sa == sb == P.OK
+    assert sa == sb and sa in (P.OK, P.WARN_DUST)
     assert b.steps_done == 4
     for cl in b.classes():
         assert all(cap > 0 for cap in cl["caps"][:2])
@@ -136,7 +137,7 @@ def test_graph_fp32_learned(P):
     for m in range(len(cs)):
         print(m, cs[m].n, "eager", ia[m]["pcg_iters"], ia[m]["refinements"], "graph",
               ib[m]["pcg_iters"], ib[m]["refinements"], ib[m]["pcg_relres"], ib[m]["flags"])
-    assert sa in (P.OK, P.WARN_GUESS_FALLBACK) and sb in (P.OK, P.WARN_GUESS_FALLBACK)
+    assert sa in (P.OK, P.WARN_GUESS_FALLBACK, P.WARN_DUST) and sb in (P.OK, P.WARN_GUESS_FALLBACK, P.WARN_DUST)
     sb_stats = b.stats()
     for m in range(len(cs)):
         assert max(ib[m]["pcg_relres"]) <= 1e-6, ib[m]
@@ -172,7 +173,7 @@ def test_graph_keeps_audit_verdict(P):
     sb, ib = b.step(3, mode=P.ENS_GRAPH)
     assert b.steps_done == 5
     sa, ia = a.step(5, mode=P.ENS_EAGER)
-    assert sa in (P.OK, P.WARN_GUESS_FALLBACK) and sb in (P.OK, P.WARN_GUESS_FALLBACK)
+    assert sa in (P.OK, P.WARN_GUESS_FALLBACK, P.WARN_DUST) and sb in (P.OK, P.WARN_GUESS_FALLBACK, P.WARN_DUST)
     full = (1 << b.prms[0].n_corr) - 1
     mask = {}
     for cl in b.classes():
@@ -210,12 +211,12 @@ def test_bench_ensemble_configuration(P, tmp_path):
     m0 = [s["mass_gas"] for s in E.stats()]
     p0 = [s["mass_p"][0] for s in E.stats()]
     st, info = E.step(1, mode=P.ENS_EAGER)
-    assert st in (P.OK, P.WARN_GUESS_FALLBACK)
+    assert st in (P.OK, P.WARN_GUESS_FALLBACK, P.WARN_DUST)
     E.autotune(str(tmp_path / "tune.json"), force=True)
     for c in E.classes():
         assert c["cg_cells_z"] > 0      # every class runs the tiled CG kernel
     st, info = E.step(6, mode=P.ENS_GRAPH)
-    assert st in (P.OK, P.WARN_GUESS_FALLBACK), st
+    assert st in (P.OK, P.WARN_GUESS_FALLBACK, P.WARN_DUST), st
     assert E.steps_done == 7
     stats = E.stats()
     for m in range(len(cs)):
@@ -227,7 +228,7 @@ def test_bench_ensemble_configuration(P, tmp_path):
     for m in firsts:
         s = P.Solver.from_case(cs[m], **kw)
         st1, _ = s.step(7)
-        assert st1 in (P.OK, P.WARN_GUESS_FALLBACK)
+        assert st1 in (P.OK, P.WARN_GUESS_FALLBACK, P.WARN_DUST)
         assert abs(s.t - E.times()[m]) <= 1e-4 * s.t
         ua = s.get(P.FIELD_U).cpu().numpy()
         ub = E.get(m, P.FIELD_U).cpu().numpy()
@@ -249,7 +250,7 @@ def test_graph_caps_follow_iterations(P):
     first_caps = None
     for call in range(12):
         st, info = E.step(10, mode=P.ENS_GRAPH)
-        assert st == P.OK, (call, st, [i["flags"] for i in info])
+        assert st in (P.OK, P.WARN_DUST), (call, st, [i["flags"] for i in info])
         for m, i in enumerate(info):
             assert max(i["pcg_relres"]) <= 1e-6, (call, m, i)
             assert not i["flags"] & P.FLAG_PCG_MAXIT, (call, m, i)
@@ -279,7 +280,7 @@ def test_autotune_cache_round_trip(P, tmp_path):
     # tuned shapes still give converged, mass-conserving steps (graph mode)
     m0 = [s["mass_gas"] for s in e.stats()]
     st, info = e.step(3, mode=P.ENS_GRAPH)
-    assert st == P.OK
+    assert st in (P.OK, P.WARN_DUST)
     for m, i in enumerate(info):
         assert max(i["pcg_relres"]) <= 1e-8
         assert abs(i["mass_gas"] - m0[m]) <= 1e-12 * m0[m]
@@ -290,3 +291,78 @@ def test_autotune_cache_round_trip(P, tmp_path):
     key_of = lambda c: (c["block"], c["cells_z"], c["cg_cells_z"], c["tiled_cells_z"])
     assert [key_of(c) for c in e2.classes()] == [key_of(c) for c in cl]
     assert json.load(open(path)) == cache
+
+
+def test_graph_eager_graph_interleaved_fp64(P):
+    """Captured and eager calls mixed on one ensemble (GRAPH 3, EAGER 1, GRAPH 2):
+    the graphs, captured for a buffer rotation, stay in step with the eager
+    step's rotation, so the six steps are bitwise the six steps of an ensemble
+    run eagerly throughout."""
+    cs = cases()
+    kw = dict(p_tol=1e-9)
+    a = P.Ensemble(cs, **kw)
+    b = P.Ensemble(cs, **kw)
+    for _ in range(6):
+        sa, ia = a.step(1, mode=P.ENS_EAGER)
+    for nst, mode in ((3, P.ENS_GRAPH), (1, P.ENS_EAGER), (2, P.ENS_GRAPH)):
+        sb, ib = b.step(nst, mode=mode)
+        assert sb in (P.OK, P.WARN_DUST)
+    assert b.steps_done == 6
+    for m in range(len(cs)):
+        assert ia[m]["pcg_iters"] == ib[m]["pcg_iters"], m
+        assert ia[m]["t"] == ib[m]["t"]
+        fa = fields(P, lambda bits: a.fields(m, bits))
+        fb = fields(P, lambda bits: b.fields(m, bits))
+        for k in fa:
+            assert np.array_equal(fa[k], fb[k]), (m, k)
+
+
+def test_graph_member_matches_oracle(P, ora):
+    """A member stepped by captured graphs against the FP64 oracle directly (the
+    graph's solves run to a fixed iteration cap, each member stopping at its
+    own convergence, so the iterates are the oracle's)."""
+    from test_gpu_parity import compare_state
+    cs = cases()
+    kw = dict(p_tol=1e-8)
+    ens = P.Ensemble(cs, **kw)
+    o = ora.Oracle.from_case(cs[2], **kw)
+    st, infos = ens.step(4, mode=P.ENS_GRAPH)
+    st_o, info_o = o.step(4)
+    assert st in (P.OK, P.WARN_DUST) and st_o in (P.OK, P.WARN_DUST)
+    assert infos[2]["pcg_iters"] == info_o[-1]["pcg_iters"]
+
+    class View:
+        def fields(self, bits):
+            return ens.fields(2, bits)
+    compare_state(P, ora, View(), o, label="graph member")
+
+
+def test_captured_solve_at_cap_reports_its_residual(P, ora):
+    """One long captured call on a decaying flow: the CG iterations a solve
+    needs outgrow the caps the graph was built with (+25 % + 2 of the first
+    step's), so the last steps stop their solves at the cap.  The launch at the
+    cap brings x up to date, so the relative residual the step reports is that
+    of the solution it applies: ||b - M x|| / ||b|| from the captured system,
+    with M rebuilt from the captured w and diagonal."""
+    import math
+    case = make_hit_case(32, 41, mach=0.2, stokes=(0.1,))
+    ens = P.Ensemble([case], p_tol=1e-10, capture=True)
+    st, info = ens.step(1, mode=P.ENS_GRAPH)
+    st, info = ens.step(150, mode=P.ENS_GRAPH)
+    assert st >= 0
+    hit = bool(info[0]["flags"] & P.FLAG_PCG_MAXIT)
+    f = ens.fields(0, P.FIELD_PSOLVE_B | P.FIELD_PSOLVE_X | P.FIELD_PSOLVE_DIAG | P.FIELD_PSOLVE_W)
+    b, x, diag, w = (f[k].cpu().numpy() for k in (P.FIELD_PSOLVE_B, P.FIELD_PSOLVE_X,
+                                                   P.FIELD_PSOLVE_DIAG, P.FIELD_PSOLVE_W))
+    n = case.n
+    h = 2 * math.pi / n
+    K = ora.kfaces(w)
+    ksum = sum(K[d] + np.roll(K[d], 1, axis=2 - d) for d in range(3))
+    psidt = diag - ksum / h ** 2
+    r = b - ora.helm_apply(psidt, K, x)
+    true_rel = np.linalg.norm(r) / np.linalg.norm(b)
+    reported = info[0]["pcg_relres"][0]
+    print(f"cap reached {hit}: corrector-1 relres reported {reported:.3e}, of x {true_rel:.3e}, "
+          f"caps {[c['caps'][:2] for c in ens.classes()]}")
+    assert hit, "the caps were not reached: the test does not exercise the cap"
+    assert abs(true_rel / reported - 1) < 1e-2

@@ -60,7 +60,7 @@ def test_fp32_vs_oracle(P, ora, n, steps):
     s = P.Solver.from_case(case, p_tol=tol, precision=P.FP32_REFINED, inner_tol=1e-7)
     o.step(steps)
     st, info = s.step(steps)
-    assert st == 0
+    assert st in (P.OK, P.WARN_DUST)
     for i in info:
         assert all(r <= tol for r in i["pcg_relres"]), i
         assert all(k >= 1 for k in i["refinements"]), i
@@ -76,7 +76,7 @@ def test_fp32_bench_workload_vs_oracle(P, ora):
     s = P.Solver.from_case(case, p_tol=tol, precision=P.FP32_REFINED, inner_tol=1e-6)
     o.step(1)
     st, info = s.step(1)
-    assert st == 0
+    assert st in (P.OK, P.WARN_DUST)
     for i in info:
         assert all(r <= tol for r in i["pcg_relres"]), i
     check_fields(P, ora, s, o, FIELD_TOL)
@@ -90,7 +90,7 @@ def test_fp32_mass_budget(P):
     s = P.Solver.from_case(case, p_tol=1e-6, precision=P.FP32_REFINED)
     m0 = s.stats()
     st, info = s.step(30)
-    assert st == 0
+    assert st in (P.OK, P.WARN_DUST)
     for k, i in enumerate(info, start=1):
         bound = 8 * EPS32 * np.sqrt(k / case.n ** 3)
         assert abs(i["mass_gas"] / m0["mass_gas"] - 1) < bound
@@ -112,7 +112,7 @@ def test_fp32_statistics_within_calibrated_spread(P):
     worst = {}
     for _ in range(6):
         for s in (a, b, f):
-            assert s.step(10)[0] == 0
+            assert s.step(10)[0] in (P.OK, P.WARN_DUST)
         sa, sb, sf = a.stats(), b.stats(), f.stats()
         for key, ga, gb, gf in (("ke", sa["ke"], sb["ke"], sf["ke"]),
                                 ("enstrophy", sa["enstrophy"], sb["enstrophy"], sf["enstrophy"]),
@@ -123,3 +123,38 @@ def test_fp32_statistics_within_calibrated_spread(P):
             assert err <= bound, (key, err, delta)
             worst[key] = max(worst.get(key, 0.0), err / bound)
     print("worst error / bound:", worst)
+
+
+def test_fp32_statistics_config3_256(P):
+    """The precision configuration at size: 256^3, Mach 0.2, one class at Stokes
+    0.2, residual 1e-6, 200 steps.  Energy, enstrophy and concentration
+    variance of the FP32-refined run against the FP64 run of the same seed,
+    every 20 steps, within max(3 x the chaotic spread of an FP64 run whose
+    initial velocity is perturbed by 1e-7, the floors 1e-5 / 1e-4 / 1e-3); the
+    errors per statistic are printed."""
+    case = make_hit_case(256, 0, mach=0.2, stokes=(0.2,))
+    kw = dict(gamma=case.gamma, C_=case.C, mu=case.mu, tau_p=case.tau_p, p_tol=1e-6)
+    a = P.Solver(case.n, case.rho, case.u, case.rho_p, **kw)
+    b = P.Solver(case.n, case.rho, case.u * (1 + 1e-7), case.rho_p, **kw)
+    f = P.Solver(case.n, case.rho, case.u, case.rho_p, precision=P.FP32_REFINED, inner_tol=1e-6,
+                 **kw)
+    floors = dict(ke=1e-5, enstrophy=1e-4, conc=1e-3)
+    worst = {}
+    for k in range(10):
+        for s in (a, b, f):
+            st, info = s.step(20)
+            assert st in (P.OK, P.WARN_DUST)
+            assert all(max(i["pcg_relres"]) <= 1e-6 for i in info)
+        sa, sb, sf = a.stats(), b.stats(), f.stats()
+        line = []
+        for key, ga, gb, gf in (("ke", sa["ke"], sb["ke"], sf["ke"]),
+                                ("enstrophy", sa["enstrophy"], sb["enstrophy"], sf["enstrophy"]),
+                                ("conc", sa["conc_var"][0], sb["conc_var"][0], sf["conc_var"][0])):
+            delta = abs(gb - ga) / abs(ga)
+            err = abs(gf - ga) / abs(ga)
+            bound = max(3 * delta, floors[key])
+            assert err <= bound, (k, key, err, delta)
+            worst[key] = max(worst.get(key, 0.0), err / bound)
+            line.append(f"{key} err {err:.2e} spread {delta:.2e}")
+        print(f"256^3 step {20 * (k + 1)} t {a.t:.4f}: " + "; ".join(line), flush=True)
+    print("256^3 worst error / bound:", worst)

@@ -1,0 +1,158 @@
+"""The learned initial guess inside the step, part by part against the oracle,
+and what it gains over the method without it.
+
+* inputs: pisoc_net_inputs on the oracle's captured pressure system against
+  the oracle's input scaling, to FP32 rounding;
+* in the step (corrector 1 of the first step, whose system is the oracle's to
+  rounding): the network's guess g against the FP64 oracle network on the same
+  BF16 inputs (the forward bar, 2e-2 relative L2), and the solve's start x0
+  against the oracle's alpha = g.b / g.(M g) and fallback rule applied to the
+  GPU's g on the oracle's operator;
+* a network that predicts nothing (zero weights) falls back in every solve,
+  and the step is then the zero-guess step;
+* gain: with the committed weights (trained at 32^3 on seeds 0-19), unseen
+  seeds 20-24 at 32^3 need fewer CG iterations in total at the same residual
+  1e-6 than the zero guess; the 128^3 and 256^3 outcome is printed.
+"""
+import numpy as np
+import pytest
+
+from paper_1404_0959_amd.inputs import make_hit_case
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1404_0959_amd.pisoc as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def weights(P):
+    from paper_1404_0959_amd.learn import load_weights
+    return load_weights()
+
+
+def bf16(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+def dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def test_net_inputs_vs_oracle(P, ora):
+    case = make_hit_case(32, 3, mach=0.2, stokes=(0.1,))
+    o = ora.Oracle.from_case(case, p_tol=1e-8, capture=True)
+    o.step(2)
+    b, diag, p0 = o.get(ora.SYS_B), o.get(ora.SYS_DIAG), o.get(ora.SYS_P0)
+    want, (s1, s2) = ora.net_inputs(b, diag, p0)
+    x, _, (g1, g2) = P.net_inputs(dev(b), dev(diag), dev(p0))
+    got = x.cpu().numpy().astype(np.float64)
+    assert abs(g1 / s1 - 1) <= 1e-13 and abs(g2 / s2 - 1) <= 1e-10, (g1, s1, g2, s2)
+    # one FP32 rounding of each value (plus the FP64 arithmetic before it)
+    err = np.abs(got - want) / (np.abs(want) + 1e-30)
+    print(f"net inputs: max relative error {err.max():.2e} (FP32 eps {EPS32:.2e})")
+    assert np.all(np.abs(got - want) <= EPS32 * np.abs(want) + 1e-12)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_guess_start_vs_oracle(P, ora, weights, precision):
+    case = make_hit_case(32, 22, mach=0.2, stokes=(0.1,))
+    kw = dict(p_tol=1e-6) if precision == "fp64" else dict(
+        p_tol=1e-6, precision=P.FP32_REFINED, inner_tol=1e-6)
+    o = ora.Oracle.from_case(case, p_tol=1e-6, capture=True)
+    s = P.Solver.from_case(case, capture=True, guess=P.GUESS_LEARNED,
+                           guess_weights=weights.data_ptr(), **kw)
+    o.step(1)
+    st, info = s.step(1)
+    assert st in (P.OK, P.WARN_GUESS_FALLBACK, P.WARN_DUST)
+    f = s.fields(P.FIELD_PSOLVE_B | P.FIELD_PSOLVE_DIAG | P.FIELD_P_PREV | P.FIELD_GUESS |
+                 P.FIELD_GUESS_X0)
+    b, diag, p0 = (f[k].cpu().numpy() for k in (P.FIELD_PSOLVE_B, P.FIELD_PSOLVE_DIAG,
+                                                 P.FIELD_P_PREV))
+    g, x0 = f[P.FIELD_GUESS].cpu().numpy(), f[P.FIELD_GUESS_X0].cpu().numpy()
+    # the network on the same BF16 inputs (FP64 oracle network, BF16 weights)
+    xin, (s1, _) = ora.net_inputs(b, diag, p0)
+    n = case.n
+    y = ora.conv_forward(bf16(weights.cpu().numpy()).astype(np.float64),
+                         bf16(xin).astype(np.float64).reshape(1, n, n, n, 2))[0]
+    rel = np.linalg.norm(g - s1 * y) / np.linalg.norm(s1 * y)
+    # the start: the oracle's rule on its own operator, applied to the GPU's g
+    x0o, alpha, ratio, fell = ora.guess_start(o.get(ora.SYS_PSIDT, 0), o.get(ora.SYS_K, 0),
+                                              b, g)
+    gpu_fell = bool(info[0]["flags"] & P.FLAG_GUESS_FALLBACK)
+    print(f"{precision}: network rel L2 {rel:.2e}; alpha {alpha:.6f}, start residual ratio "
+          f"{ratio:.4f}, fallback oracle {fell} gpu {gpu_fell}")
+    assert rel <= 2e-2
+    assert fell == gpu_fell
+    tol = 1e-9 if precision == "fp64" else 1e-5
+    assert np.max(np.abs(x0 - x0o)) <= tol * max(np.max(np.abs(x0o)), 1e-300)
+    # an FP32 step carries the FP64 start; in FP64 the captured b is the oracle's
+    if precision == "fp64":
+        assert np.max(np.abs(b - o.get(ora.SYS_B, 0))) <= 1e-10 * np.max(np.abs(b))
+
+
+def test_zero_network_falls_back(P):
+    """Zero weights: g = 0, every solve falls back to x0 = 0 (flag 8, warning
+    status) and the step is the zero-guess step to rounding."""
+    import torch
+    case = make_hit_case(32, 4, mach=0.2, stokes=(0.1,))
+    w0 = torch.zeros(P.NET_NWEIGHTS, dtype=torch.float32, device="cuda")
+    a = P.Solver.from_case(case, p_tol=1e-8)
+    b = P.Solver.from_case(case, p_tol=1e-8, guess=P.GUESS_LEARNED, guess_weights=w0.data_ptr(),
+                           capture=True)
+    sa, ia = a.step(3)
+    sb, ib = b.step(3)
+    assert sa in (P.OK, P.WARN_DUST) and sb == P.WARN_GUESS_FALLBACK
+    assert all(i["flags"] & P.FLAG_GUESS_FALLBACK for i in ib)
+    assert [i["pcg_iters"] for i in ia] == [i["pcg_iters"] for i in ib]
+    assert float(b.get(P.FIELD_GUESS_X0).abs().max()) == 0.0
+    for bit in (P.FIELD_RHO, P.FIELD_U, P.FIELD_RHO_P):
+        fa, fb = a.get(bit).cpu().numpy(), b.get(bit).cpu().numpy()
+        spread = np.max(np.abs(fa - fa.mean()))
+        assert np.max(np.abs(fa - fb)) <= 1e-12 * spread, bit
+
+
+def iterations(P, case, steps, weights=None, **kw):
+    extra = {} if weights is None else dict(guess=P.GUESS_LEARNED, guess_weights=weights.data_ptr())
+    s = P.Solver.from_case(case, p_tol=1e-6, **kw, **extra)
+    st, info = s.step(steps)
+    assert st >= 0
+    for i in info:
+        assert max(i["pcg_relres"]) <= 1e-6, i
+    return sum(sum(i["pcg_iters"]) for i in info)
+
+
+def test_learned_guess_gain_unseen_seeds(P, weights):
+    """Total CG iterations over 10 steps of each unseen seed 20-24 at 32^3
+    (the training size), at residual 1e-6, FP64: the guess must save at
+    least 5 % of the zero-guess iterations."""
+    zero = learned = 0
+    for seed in range(20, 25):
+        case = make_hit_case(32, seed, mach=0.2, stokes=(0.1,))
+        z = iterations(P, case, 10)
+        g = iterations(P, case, 10, weights)
+        print(f"32^3 seed {seed}: zero {z}, learned {g}")
+        zero += z
+        learned += g
+    print(f"32^3 seeds 20-24: zero {zero}, learned {learned} ({learned / zero - 1:+.1%})")
+    assert learned <= 0.95 * zero
+    for n, steps in ((128, 5), (256, 3)):
+        case = make_hit_case(n, 20, mach=0.2, stokes=(0.2,))
+        for prec, kw in (("fp64", {}), ("fp32", dict(precision=P.FP32_REFINED, inner_tol=1e-6))):
+            z = iterations(P, case, steps, **kw)
+            g = iterations(P, case, steps, weights, **kw)
+            print(f"{n}^3 seed 20 {prec}, {steps} steps: zero {z}, learned {g} "
+                  f"({g / z - 1:+.1%})")

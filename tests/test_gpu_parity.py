@@ -1,14 +1,22 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 Fields are compared element by element with two bounds: max|f_gpu - f_oracle|
-<= 1e-10 max|f_oracle| (FP64 agreement to 1e-10 relative), and <= 1e-8 of the
-field's spread max|f - <f>|, so that the deviations from the mean -- the part
-that carries the physics when a field starts uniform -- agree to 8 digits.
-(The oracle stores absolute densities and loses digits in rho_k - rho^n; the
-GPU path stores deviations; their difference is a few thousand FP64 ulps of
-the magnitude.)  The CG iteration counts must match exactly.  Sizes span
+<= 1e-10 max|f_oracle| (FP64 agreement to 1e-10 relative), and <= 1e-10 of the
+field's spread max|f - <f>| (the deviation-normalised parity reading), so
+that the deviations from the mean -- the part that carries the physics when a
+field starts uniform -- agree to 10 digits.  Every comparison prints both
+measured errors.  The CG iteration counts must match exactly.  Sizes span
 several blocks with ragged tails (40, 70), the minimum grid (8) and the
 decaying-HIT configuration at 32^3.
+
+Three comparisons take a wider spread bound, each set a few times above its
+measured error: one step from a uniform density at 64^3 and 128^3 (measured
+2.4e-11 and 1.4e-10 of the spread; bound 1e-9) and at 256^3 at residual 1e-6
+(measured 9.5e-9; bound 3e-8).  After one step from rest the density spread
+is only what one step of compression builds, while the two sides' CG
+iterates differ by the order of their FP64 dot products, which grows with the
+number of summed cells (the magnitude-normalised errors stay at 1e-12 or
+less).
 """
 import math
 
@@ -32,19 +40,29 @@ def P():
     return P
 
 
-def dev_err(g, o):
-    """max|g - o| in units of the pass mark: 1.0 = min(1e-10 |o|max, 1e-8 spread)
-    reached; the returned value is scaled so that TOL is the pass mark."""
+SPREAD_TOL = 1e-10
+
+
+def raw_err(g, o):
+    """(max|g - o| / max|o - <o>|, max|g - o| / max|o|): the deviation-normalised
+    error of the parity reading and the magnitude-normalised one."""
     g = np.asarray(g)
     o = np.asarray(o)
-    d = np.max(np.abs(g - o))
-    mag = np.max(np.abs(o))
-    spread = np.max(np.abs(o - o.mean()))
-    if d == 0.0:
+    d = float(np.max(np.abs(g - o)))
+    mag = float(np.max(np.abs(o)))
+    spread = float(np.max(np.abs(o - o.mean())))
+    r_dev = d / spread if spread > 0 else (0.0 if d == 0.0 else np.inf)
+    r_mag = d / mag if mag > 0 else (0.0 if d == 0.0 else np.inf)
+    return r_dev, r_mag
+
+
+def dev_err(g, o, spread_tol=SPREAD_TOL):
+    """max|g - o| in units of the pass mark: 1.0 = min(TOL |o|max, spread_tol
+    spread) reached; the returned value is scaled so that TOL is the pass mark."""
+    r_dev, r_mag = raw_err(g, o)
+    if r_dev == 0.0 and r_mag == 0.0:
         return 0.0
-    r_mag = d / (1e-10 * mag) if mag > 0 else np.inf
-    r_dev = d / (1e-8 * spread) if spread > 0 else (0.0 if d <= 1e-10 * mag else np.inf)
-    return float(TOL * max(r_mag, r_dev))
+    return float(TOL * max(r_mag / TOL, r_dev / spread_tol))
 
 
 def to_np(t):
@@ -56,18 +74,22 @@ def gpu_fields(P, s):
     return {k: to_np(v) for k, v in f.items()}
 
 
-def compare_state(P, ora, s, o, tol=TOL):
+def compare_state(P, ora, s, o, tol=TOL, label="", spread_tol=SPREAD_TOL):
+    """Every field within the pass mark; the measured deviation- and
+    magnitude-normalised errors are printed per field."""
     g = gpu_fields(P, s)
-    errs = {
-        "rho": dev_err(g[P.FIELD_RHO], o.get(ora.RHO)),
-        "u": dev_err(g[P.FIELD_U], o.get(ora.U)),
-        "phi": dev_err(g[P.FIELD_PHI], o.get(ora.PHI)),
-        "p": dev_err(g[P.FIELD_P], o.get(ora.P)),
-    }
-    if o.K:
-        errs["rho_p"] = max(dev_err(g[P.FIELD_RHO_P][c], o.get(ora.RHO_P)[c]) for c in range(o.K))
+    pairs = {"rho": (g[P.FIELD_RHO], o.get(ora.RHO)), "u": (g[P.FIELD_U], o.get(ora.U)),
+             "phi": (g[P.FIELD_PHI], o.get(ora.PHI)), "p": (g[P.FIELD_P], o.get(ora.P))}
+    for c in range(o.K):
+        pairs[f"rho_p{c}"] = (g[P.FIELD_RHO_P][c], o.get(ora.RHO_P)[c])
+    errs, raw = {}, {}
+    for k, (a, b) in pairs.items():
+        errs[k] = dev_err(a, b, spread_tol)
+        raw[k] = raw_err(a, b)
+    print(f"parity {label}: " + ", ".join(f"{k} dev {d:.2e} mag {m:.2e}"
+                                         for k, (d, m) in raw.items()), flush=True)
     bad = {k: v for k, v in errs.items() if not v <= tol}
-    assert not bad, errs
+    assert not bad, (errs, raw)
     return errs
 
 
@@ -126,14 +148,23 @@ def test_helm_solve_edges(P, ora):
 
 
 # ------------------------------------------------------------ whole step
+# step flags both sides define alike: solve cap, non-finite / non-positive gas,
+# and the three dust flags
+SHARED_FLAGS = 1 | 2 | 4 | 64 | 128 | 256
+
+
 def run_pair(P, ora, case, steps, **kw):
+    """The same steps on the oracle and the GPU: equal status (OK, or the dust
+    warning where the method's central fluxes undershoot), equal flags, CG
+    iteration counts and time steps per step."""
     o = ora.Oracle.from_case(case, **kw)
     s = P.Solver.from_case(case, **kw)
     st_o, info_o = o.step(steps)
     st_g, info_g = s.step(steps)
-    assert st_o == st_g == 0
+    assert st_o == st_g and st_o in (P.OK, P.WARN_DUST), (st_o, st_g)
     for a, b in zip(info_o, info_g):
         assert a["pcg_iters"] == b["pcg_iters"], (a, b)
+        assert a["flags"] & SHARED_FLAGS == b["flags"] & SHARED_FLAGS, (a["flags"], b["flags"])
         assert abs(a["dt"] - b["dt"]) <= 1e-10 * a["dt"]
         assert abs(a["mass_gas"] - b["mass_gas"]) <= 1e-12 * a["mass_gas"]
     return o, s, info_o, info_g
@@ -143,7 +174,7 @@ def test_step_parity_hit32_one_step(P, ora):
     """Decaying HIT, 32^3, Mach 0.2, one class at Stokes 0.1, CFL 0.5, tol 1e-8."""
     case = make_hit_case(32, 0, mach=0.2, stokes=(0.1,))
     o, s, io, ig = run_pair(P, ora, case, 1, p_tol=1e-8)
-    compare_state(P, ora, s, o)
+    compare_state(P, ora, s, o, label="hit32 1 step")
 
 
 def test_step_parity_hit32_100_steps(P, ora):
@@ -151,7 +182,7 @@ def test_step_parity_hit32_100_steps(P, ora):
     identical CG iteration counts at every corrector of every step."""
     case = make_hit_case(32, 0, mach=0.2, stokes=(0.1,))
     o, s, io, ig = run_pair(P, ora, case, 100, p_tol=1e-8)
-    compare_state(P, ora, s, o)
+    compare_state(P, ora, s, o, label="hit32 100 steps")
     assert abs(s.t - o.t) <= 1e-12 * o.t
 
 
@@ -159,7 +190,7 @@ def test_step_parity_hit32_100_steps(P, ora):
 def test_step_parity_ragged_and_small(P, ora, n, classes, steps):
     case = make_hit_case(n, 11, mach=0.5, stokes=classes)
     o, s, io, ig = run_pair(P, ora, case, steps, p_tol=1e-9)
-    compare_state(P, ora, s, o)
+    compare_state(P, ora, s, o, label="ragged/small")
 
 
 @pytest.mark.parametrize("n", [64, 128])
@@ -168,7 +199,7 @@ def test_step_parity_hit128_tiled(P, ora, n):
     spans x and its x halo wraps onto itself)."""
     case = make_hit_case(n, 3, mach=0.2, stokes=(0.2,))
     o, s, io, ig = run_pair(P, ora, case, 2, p_tol=1e-8)
-    compare_state(P, ora, s, o)
+    compare_state(P, ora, s, o, label="tiled 64/128", spread_tol=1e-9)
 
 
 @pytest.mark.parametrize("n", [32, 48, 64, 128])
@@ -194,8 +225,8 @@ def test_tiled_kernels_match_gathered(P, monkeypatch, precision, n):
             monkeypatch.setenv("PISOC_UNTILED", "1")
         s = P.Solver.from_case(case, **kw)
         st, info = s.step(2)
-        assert st == 0
-        runs.append((gpu_fields(P, s), [i["pcg_iters"] for i in info],
+        assert st in (P.OK, P.WARN_DUST)
+        runs.append((gpu_fields(P, s), [(i["pcg_iters"], i["flags"]) for i in info],
                      [i["mass_gas"] for i in info], [i["dt"] for i in info]))
         monkeypatch.delenv("PISOC_UNTILED", raising=False)
     (fa, ia, ma, da), (fb, ib, mb, db) = runs
@@ -218,7 +249,7 @@ def test_step_parity_hit256_bench_workload(P, ora):
     the tiled CG kernel and the LDS-tiled momentum sweeps."""
     case = make_hit_case(256, 0, mach=0.2, stokes=(0.2,))
     o, s, io, ig = run_pair(P, ora, case, 1, p_tol=1e-6)
-    compare_state(P, ora, s, o)
+    compare_state(P, ora, s, o, label="hit256 bench workload", spread_tol=3e-8)
 
 
 def test_step_parity_options(P, ora):
@@ -226,9 +257,9 @@ def test_step_parity_options(P, ora):
     case = make_hit_case(24, 5, mach=0.2, stokes=(0.0, 0.3))
     o, s, io, ig = run_pair(P, ora, case, 2, p_tol=1e-10, n_corr=3, n_mom_sweeps=2,
                             n_dust_sweeps=6, dt_fixed=0.004)
-    compare_state(P, ora, s, o)
+    compare_state(P, ora, s, o, label="options 1")
     o, s, io, ig = run_pair(P, ora, case, 3, p_tol=1e-9, n_corr=1, dt_max=0.003, cfl=0.8)
-    compare_state(P, ora, s, o)
+    compare_state(P, ora, s, o, label="options 2")
 
 
 def test_captured_pressure_system_parity(P, ora):
@@ -241,6 +272,7 @@ def test_captured_pressure_system_parity(P, ora):
     pairs = [(P.FIELD_PSOLVE_B, ora.SYS_B), (P.FIELD_PSOLVE_X, ora.SYS_X),
              (P.FIELD_P_PREV, ora.SYS_P0), (P.FIELD_PSOLVE_DIAG, ora.SYS_DIAG)]
     for fb, ob in pairs:
+        print(f"captured system field {fb}: dev {raw_err(to_np(f[fb]), o.get(ob, corr=0))[0]:.2e}")
         assert dev_err(to_np(f[fb]), o.get(ob, corr=0)) <= TOL, fb
 
 
@@ -270,12 +302,12 @@ def test_gpu_mass_conservation_and_determinism(P):
         s = P.Solver.from_case(case, p_tol=1e-8)
         s0 = s.stats()
         st, info = s.step(10)
-        assert st == 0
+        assert st in (P.OK, P.WARN_DUST)
         for i in info:
             assert abs(i["mass_gas"] / s0["mass_gas"] - 1) <= 1e-13
             for c in range(2):
                 assert abs(i["mass_p"][c] / s0["mass_p"][c] - 1) <= 1e-13
-        runs.append((gpu_fields(P, s), [i["pcg_iters"] for i in info]))
+        runs.append((gpu_fields(P, s), [(i["pcg_iters"], i["flags"]) for i in info]))
     (fa, ia), (fb, ib) = runs
     assert ia == ib
     for k in fa:
@@ -295,6 +327,7 @@ def test_gpu_translation_equivariance(P):
     s2.step(2)
     f1, f2 = gpu_fields(P, s1), gpu_fields(P, s2)
     for k in f1:
+        print(f"translated field {k}: dev {raw_err(roll(f1[k]), f2[k])[0]:.2e}")
         assert dev_err(roll(f1[k]), f2[k]) <= 1e-11, k
 
 
@@ -345,7 +378,7 @@ def test_gpu_error_paths(P, ora):
     stg, ig = g.step(1)
     assert sto == stg == P.WARN_NOT_CONVERGED
     assert ig[0]["pcg_iters"] == [2, 2] and ig[0]["flags"] & P.FLAG_PCG_MAXIT
-    compare_state(P, ora, g, o)
+    compare_state(P, ora, g, o, label="iteration cap")
     # a non-finite velocity: the step is rejected and the state kept
     u2 = case.u.copy()
     u2[0, 3, 4, 5] = np.nan
@@ -358,3 +391,101 @@ def test_gpu_error_paths(P, ora):
                     tau_p=case.tau_p, p_tol=1e-8, p_maxit=50)
     sto, _ = o2.step(1)
     assert sto == ora.ERR_DIVERGED
+
+
+# ------------------------------------------------------------ configurations at size
+def test_config2_128_three_classes(P, ora):
+    """The 128^3 configuration: Mach 0.5, three dust classes at Stokes 0.05, 0.2
+    and 0.5, adaptive dt at CFL 0.5, over 10 steps: fields, flags and CG
+    counts as the oracle's at every step, and the statistics of the
+    configuration (energy, enstrophy, concentration variance of each class)
+    at steps 0 and 10."""
+    case = make_hit_case(128, 0, mach=0.5, stokes=(0.05, 0.2, 0.5))
+    o = ora.Oracle.from_case(case, p_tol=1e-8)
+    s = P.Solver.from_case(case, p_tol=1e-8)
+    for k in range(2):
+        so, sg = o.stats(), s.stats()
+        for key in ("ke", "enstrophy", "rho_rms", "mach_rms"):
+            if so[key] == 0.0:      # the initial density is uniform
+                assert abs(sg[key]) < 1e-14, (k, key, sg[key])
+            else:
+                assert abs(sg[key] / so[key] - 1) <= 1e-10, (k, key, sg[key], so[key])
+        for c in range(3):
+            assert abs(sg["conc_var"][c] - so["conc_var"][c]) <= 1e-10 * max(so["conc_var"][c], 1e-12)
+        if k == 0:
+            st_o, io = o.step(10)
+            st_g, ig = s.step(10)
+            assert st_o == st_g and st_o in (P.OK, P.WARN_DUST)
+            for a, b in zip(io, ig):
+                assert a["pcg_iters"] == b["pcg_iters"], (a, b)
+                assert a["flags"] & SHARED_FLAGS == b["flags"] & SHARED_FLAGS
+    compare_state(P, ora, s, o, label="config2 128^3 10 steps")
+
+
+def test_predictor_stage_parity(P, ora):
+    """The momentum predictor's output u* (before the correctors) of the first
+    and of the third step, against the oracle's."""
+    case = make_hit_case(40, 8, mach=0.5, stokes=(0.2,))
+    o = ora.Oracle.from_case(case, p_tol=1e-10, capture=True)
+    s = P.Solver.from_case(case, p_tol=1e-10, capture=True)
+    for steps in (1, 2):
+        o.step(steps)
+        s.step(steps)
+        got = to_np(s.get(P.FIELD_USTAR))
+        want = o.get(ora.SYS_USTAR)
+        r_dev, r_mag = raw_err(got, want)
+        print(f"u* after {steps} more step(s): dev {r_dev:.2e} mag {r_mag:.2e}", flush=True)
+        assert dev_err(got, want) <= TOL
+
+
+# ------------------------------------------------------------ dust flags
+def grid(n):
+    h = 2 * math.pi / n
+    xc = (np.arange(n) + 0.5) * h
+    z, y, x = np.meshgrid(xc, xc, xc, indexing="ij")
+    return x, y, z
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dust_flags_as_oracle(P, ora, precision):
+    """The oracle's three forced dust cases on the GPU: a dust front in a
+    uniform flow undershoots (flag 64, warning); a NaN in the dust input is
+    rejected (flag 128, error, state kept); in a Taylor-Green vortex the
+    implicit diagonal turns non-positive above tau* = 8/(9 dt) (flag 256)."""
+    kw = {} if precision == "fp64" else dict(precision=P.FP32_REFINED, inner_tol=1e-7)
+    tolkw = dict(p_tol=1e-12) if precision == "fp64" else dict(p_tol=1e-7)
+    n = 16
+    x, y, z = grid(n)
+    rho = np.ones((n, n, n))
+    u = np.stack([np.full((n, n, n), 0.5), np.zeros((n, n, n)), np.zeros((n, n, n))])
+    front = (1e-3 * (x < math.pi))[None]
+    o = ora.Oracle(n, rho, u, front, gamma=1.4, C_=10.0, mu=1e-3, tau_p=(0.1,), dt_fixed=0.05,
+                   **tolkw)
+    g = P.Solver(n, rho, u, front, gamma=1.4, C_=10.0, mu=1e-3, tau_p=(0.1,), dt_fixed=0.05,
+                 **tolkw, **kw)
+    sto, io = o.step(1)
+    stg, ig = g.step(1)
+    assert sto == stg == P.WARN_DUST
+    assert io[0]["flags"] & SHARED_FLAGS == ig[0]["flags"] & SHARED_FLAGS == P.FLAG_DUST_NEG
+    assert to_np(g.get(P.FIELD_RHO_P)).min() < 0.0
+    # a NaN in the dust input
+    rp = np.full((1, n, n, n), 1e-3)
+    rp[0, 2, 3, 4] = np.nan
+    g = P.Solver(n, rho, u, rp, gamma=1.4, C_=10.0, mu=1e-3, tau_p=(0.1,), dt_fixed=0.05,
+                 **tolkw, **kw)
+    stg, ig = g.step(1, raise_on_error=False)
+    assert stg == P.ERR_DIVERGED and g.t == 0.0
+    # the implicit diagonal in a Taylor-Green vortex
+    nt, dt = 32, 0.01
+    tg = taylor_green_case(n=nt, mach=0.05, nu=1e-3)
+    for factor, flagged in ((0.8, False), (1.25, True)):
+        tau = factor * 8.0 / (9.0 * dt)
+        rpt = (1e-3 * tg["rho"])[None]
+        o = ora.Oracle(nt, tg["rho"], tg["u"], rpt, gamma=tg["gamma"], C_=tg["C"], mu=tg["mu"],
+                       tau_p=(tau,), dt_fixed=dt, **tolkw)
+        g = P.Solver(nt, tg["rho"], tg["u"], rpt, gamma=tg["gamma"], C_=tg["C"], mu=tg["mu"],
+                     tau_p=(tau,), dt_fixed=dt, **tolkw, **kw)
+        sto, io = o.step(1)
+        stg, ig = g.step(1)
+        assert bool(ig[0]["flags"] & P.FLAG_DUST_DIAG) == flagged
+        assert io[0]["flags"] & 256 == ig[0]["flags"] & 256

@@ -40,7 +40,7 @@ def test_profile_counts_cg_iterations(P):
     prof = s.profile_read()
     s.profile(False)
     s.close()
-    assert st == P.OK and len(info) == 3
+    assert st in (P.OK, P.WARN_DUST) and len(info) == 3
     iters = [it for i in info for it in i["pcg_iters"]]
     assert all(it > 0 for it in iters)
     cg = prof["k_pcg_spmv"]
