@@ -352,6 +352,25 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
                               void* d_workspace, size_t ws_bytes, void* hip_stream,
                               int32_t* iters, double* relres);
 
+/* The pressure solve of pisoc_helm_solve for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same kernels and results, but the scratch comes
+ * from a file-scope device array of PISOC_HELM_NOALLOC_BYTES that each GPU the
+ * library runs on holds until the process ends, not from a caller's
+ * workspace.  The call allocates nothing (no hipMalloc, hipFree, pinned host
+ * buffer or allocating library routine); its first call on a device takes the
+ * array's address there.  n <= PISOC_HELM_NOALLOC_MAX_N, else
+ * PISOC_ERR_WORKSPACE with no work done.  Every call on one GPU shares that
+ * GPU's array: calls that overlap in time on one GPU (other host threads, or
+ * other streams) race and must not be made; sequential calls are
+ * independent.  Arguments, results and the other errors as pisoc_helm_solve;
+ * synchronises. */
+#define PISOC_HELM_NOALLOC_MAX_N 64
+#define PISOC_HELM_NOALLOC_BYTES (20u << 20)
+pisoc_status pisoc_helm_solve_noalloc(int32_t n, const double* d_psidt, const double* d_w,
+                                      const double* d_b, double* d_x, double tol, int32_t maxit,
+                                      void* hip_stream, int32_t* iters, double* relres);
+
 /* ---- learned initial guess of the pressure correction --------------------
  * Not in the paper: a small network predicts the start of each pressure solve
  * from the corrector's Jacobi-scaled continuity defect and the pressure of the

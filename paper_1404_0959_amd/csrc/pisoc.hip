@@ -26,6 +26,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -2226,6 +2227,61 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
                       lay, hst, reinterpret_cast<hipStream_t>(hip_stream), iters, relres);
     (void)hipHostFree(hst);
     return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------- pressure solve without allocation
+// The scratch of pisoc_helm_solve_noalloc: the workspace pisoc_helm_solve takes
+// from its caller (solver state, reduction partials, the CG vectors), here
+// a file-scope device array of which every GPU the library runs on holds its
+// own copy until the process ends.  In host code `scratch` only names the
+// symbol: its device address on the current GPU comes from
+// hipGetSymbolAddress, taken once per device and kept in g_scratch_ptr.
+static __device__ __align__(256) char scratch[PISOC_HELM_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mtx;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's copy of `scratch`.
+pisoc_status scratch_on_current_device(char** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PISOC_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mtx);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PISOC_ERR_HIP;
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return PISOC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pisoc_status pisoc_helm_solve_noalloc(int32_t n, const double* d_psidt, const double* d_w,
+                                      const double* d_b, double* d_x, double tol, int32_t maxit,
+                                      void* hip_stream, int32_t* iters, double* relres) {
+    if (n < PISOC_MIN_N || n > PISOC_MAX_N || !d_psidt || !d_w || !d_b || !d_x ||
+        !(tol > 0.0) || !(tol < 1.0) || maxit < 1)
+        return PISOC_ERR_INVALID;
+    const Layout lay = helm_layout(n);
+    if (n > PISOC_HELM_NOALLOC_MAX_N || lay.total > sizeof(scratch)) return PISOC_ERR_WORKSPACE;
+    char* ws = nullptr;
+    const pisoc_status sp = scratch_on_current_device(&ws);
+    if (sp != PISOC_OK) return sp;
+    // every scratch value is written before it is read (the state by the copy
+    // in helm_solve_on, the partials and CG vectors by the kernels that
+    // produce them), so nothing has to be cleared between calls; the state is
+    // read back into pageable host memory, no pinned buffer is allocated
+    DevState hst{};
+    return helm_solve_on(n, d_psidt, d_w, d_b, d_x, tol, maxit, ws, lay, &hst,
+                         reinterpret_cast<hipStream_t>(hip_stream), iters, relres);
 }
 
 pisoc_status pisoc_net_inputs(int32_t n, const double* d_b, const double* d_diag,

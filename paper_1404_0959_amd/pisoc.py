@@ -32,6 +32,7 @@ EXPORTED = [
     "pisoc_workspace_bytes", "pisoc_init", "pisoc_step", "pisoc_fields", "pisoc_get_stats",
     "pisoc_time", "pisoc_steps_done", "pisoc_destroy", "pisoc_last_error", "pisoc_status_string",
     "pisoc_helm_apply", "pisoc_helm_workspace_bytes", "pisoc_helm_solve",
+    "pisoc_helm_solve_noalloc",
     "pisoc_profile", "pisoc_profile_read",
     "pisoc_net_workspace_bytes", "pisoc_net_forward", "pisoc_net_grad", "pisoc_net_adam",
     "pisoc_net_inputs",
@@ -132,6 +133,9 @@ def lib():
     L.pisoc_helm_solve.argtypes = [i32, vp, vp, vp, vp, f64, i32, vp, sz, vp,
                                    C.POINTER(i32), C.POINTER(f64)]
     L.pisoc_helm_solve.restype = C.c_int
+    L.pisoc_helm_solve_noalloc.argtypes = [i32, vp, vp, vp, vp, f64, i32, vp,
+                                           C.POINTER(i32), C.POINTER(f64)]
+    L.pisoc_helm_solve_noalloc.restype = C.c_int
     L.pisoc_profile.argtypes = [vp, i32]
     L.pisoc_profile.restype = C.c_int
     L.pisoc_profile_read.argtypes = [vp, C.POINTER(KernelStat), i32]
@@ -553,3 +557,23 @@ def helm_solve(psidt, w, b, x0=None, tol=1e-10, maxit=1000, stream=None):
         raise PisocError(st, "pisoc_helm_solve")
     return x, it.value, rel.value, st
 
+
+HELM_NOALLOC_MAX_N = 64
+
+
+def helm_solve_noalloc(psidt, w, b, x0=None, tol=1e-10, maxit=1000, stream=None):
+    """As helm_solve, through the entry point that allocates nothing (its scratch
+    is the library's own device array; grids up to HELM_NOALLOC_MAX_N).  The
+    output x is allocated here by torch, as every output of this binding is;
+    the library call itself allocates nothing."""
+    torch = _torch()
+    n = b.shape[-1]
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    it = C.c_int32(0)
+    rel = C.c_double(0.0)
+    st = lib().pisoc_helm_solve_noalloc(n, psidt.data_ptr(), w.data_ptr(), b.data_ptr(),
+                                        x.data_ptr(), tol, maxit, _stream_ptr(torch, stream),
+                                        C.byref(it), C.byref(rel))
+    if st < 0:
+        raise PisocError(st, "pisoc_helm_solve_noalloc")
+    return x, it.value, rel.value, st

@@ -102,6 +102,17 @@ def test_status_strings(lib):
         assert lib.pisoc_status_string(st) != b"unknown status"
 
 
+def test_noalloc_solve_rejects_before_gpu_work(lib):
+    """Sizes beyond the static scratch's maximum, and bad arguments, are
+    rejected before any GPU work (no device is touched here)."""
+    dummy = ctypes.c_void_p(256)
+    assert lib.pisoc_helm_solve_noalloc(P.HELM_NOALLOC_MAX_N + 16, dummy, dummy, dummy, dummy,
+                                        1e-8, 10, None, None, None) == P.ERR_WORKSPACE
+    assert lib.pisoc_helm_solve_noalloc(32, None, dummy, dummy, dummy, 1e-8, 10, None,
+                                        None, None) == P.ERR_INVALID
+    assert lib.pisoc_helm_solve_noalloc(32, dummy, dummy, dummy, dummy, 1e-8, 0, None,
+                                        None, None) == P.ERR_INVALID
+
 
 # C structs of the header and their ctypes mirrors in the binding
 STRUCTS = {"pisoc_params": P.Params, "pisoc_step_info": P.StepInfo, "pisoc_stats": P.Stats,
