@@ -371,6 +371,35 @@ pisoc_status pisoc_helm_solve_noalloc(int32_t n, const double* d_psidt, const do
                                       const double* d_b, double* d_x, double tol, int32_t maxit,
                                       void* hip_stream, int32_t* iters, double* relres);
 
+/* ---- diagnostics of the flow ----------------------------------------------
+ * The paper's validation quantities (Results section: the energy spectrum, the
+ * kinetic energy and enstrophy, the Taylor micro-scale; third figure: iso-
+ * surfaces of the second invariant Q of the velocity gradient), for a velocity
+ * field d_u (3 n^3 FP64, SoA, as pisoc_fields returns it).
+ *
+ * Spectrum: u_hat(k) = DFT(u)(k) / n^3 over the integer wavevectors with
+ * components in [-n/2, n/2); shell s holds the k with s - 1/2 <= |k| < s + 1/2;
+ * E(s) = sum over the shell of |u_hat(k)|^2 / 2, so sum_s E(s) = <|u|^2> / 2.
+ * Taylor micro-scale: lambda = sqrt(5 sum_k |u_hat|^2/2 / D) with
+ * D = sum_k |k|^2 |u_hat(k)|^2 / 2 (the isotropic lambda^2 = 15 nu u'^2 / eps,
+ * u'^2 = (2/3) sum E, eps = 2 nu D).  n must be a power of two (8..1024).
+ * Q = (|Omega|^2 - |S|^2)/2 = -(1/2) sum_ij (d_j u_i)(d_i u_j) per cell, with
+ * the Gauss-I4 derivatives of the enstrophy statistic. */
+
+/* Shells of the spectrum of an n^3 grid (0 if n is not supported). */
+int32_t pisoc_diag_spectrum_bins(int32_t n);
+/* Device workspace of pisoc_diag_spectrum and pisoc_diag_qcrit (256-byte aligned). */
+size_t pisoc_diag_workspace_bytes(int32_t n);
+/* E(s) for s = 0..nbins-1 into h_E (host), nbins = pisoc_diag_spectrum_bins(n);
+ * h_taylor, h_dsum (host, may be NULL): lambda and D.  Synchronises. */
+pisoc_status pisoc_diag_spectrum(int32_t n, const double* d_u, double* h_E, int32_t nbins,
+                                 double* h_taylor, double* h_dsum, void* d_ws, size_t ws_bytes,
+                                 void* hip_stream);
+/* Q into d_q (n^3 FP64, device).  h_means (host, may be NULL): <Q> and
+ * <(div u)^2> (Gauss-I4), then the call synchronises; else asynchronous. */
+pisoc_status pisoc_diag_qcrit(int32_t n, const double* d_u, double* d_q, double* h_means,
+                              void* d_ws, size_t ws_bytes, void* hip_stream);
+
 /* ---- learned initial guess of the pressure correction --------------------
  * Not in the paper: a small network predicts the start of each pressure solve
  * from the corrector's Jacobi-scaled continuity defect and the pressure of the

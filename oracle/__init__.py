@@ -8,6 +8,7 @@ method's equations; it shares no code with the GPU library.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -212,6 +213,66 @@ def guess_start(psidt, K, b, g):
     if st < 0:
         raise ValueError(f"ora_guess_start failed with status {st}")
     return x0, a.value, rr.value, bool(st)
+
+
+# ---------------------------------------------------------------- diagnostics
+# The paper's validation quantities of the flow (Results section: the energy
+# spectrum, the enstrophy and kinetic energy, the Taylor micro-scale; third
+# figure: iso-surfaces of the second invariant Q).  Their discrete readings:
+#  * spectrum: u_hat(k) = DFT(u)(k) / n^3 over integer wavevectors k with
+#    components in [-n/2, n/2); shell s holds the k with s - 1/2 <= |k| < s + 1/2;
+#    E(s) = sum over the shell of |u_hat(k)|^2 / 2, so that sum_s E(s) = <|u|^2>/2
+#    (Parseval);
+#  * Taylor micro-scale: lambda = sqrt(5 sum_k |u_hat|^2/2 / sum_k |k|^2 |u_hat|^2/2)
+#    (the isotropic relation lambda^2 = 15 nu u'^2 / eps with u'^2 = (2/3) int E
+#    and eps = 2 nu int k^2 E), with |k|^2 of each wavevector, not of its shell;
+#  * Q = (|Omega|^2 - |S|^2)/2 = -(1/2) sum_ij (d_j u_i)(d_i u_j) per cell, with
+#    the Gauss-I4 cell derivatives of the enstrophy statistic.
+
+
+def spectrum_bins(n):
+    """Number of shells of an n^3 grid: shell(3 (n/2)^2) + 1."""
+    return shell_index(3 * (n // 2) ** 2) + 1
+
+
+def shell_index(k2):
+    """s with s - 1/2 <= sqrt(k2) < s + 1/2 for an integer k2 >= 0 (integer arithmetic)."""
+    k2 = np.asarray(k2, dtype=np.int64)
+    s = np.floor(np.sqrt(k2.astype(np.float64))).astype(np.int64)
+    s = np.where(s * s > k2, s - 1, s)
+    s = np.where((s + 1) * (s + 1) <= k2, s + 1, s)
+    return s + (k2 >= s * s + s + 1)
+
+
+def spectrum(u):
+    """(E[shell], lambda, D) of a velocity field u [3][n][n][n]; D = sum_k |k|^2 |u_hat|^2 / 2."""
+    u = _f64(u)
+    n = u.shape[-1]
+    N = n ** 3
+    k1 = np.fft.fftfreq(n, 1.0 / n).astype(np.int64)
+    kz, ky, kx = np.meshgrid(k1, k1, k1, indexing="ij")
+    k2 = kx * kx + ky * ky + kz * kz
+    e = np.zeros((n, n, n))
+    for d in range(3):
+        uh = np.fft.fftn(u[d]) / N
+        e += 0.5 * (uh.real ** 2 + uh.imag ** 2)
+    sh = shell_index(k2)
+    E = np.bincount(sh.ravel(), weights=e.ravel(), minlength=spectrum_bins(n))
+    D = float(np.sum(k2 * e))
+    tot = float(np.sum(e))
+    lam = math.sqrt(5.0 * tot / D) if D > 0 else 0.0
+    return E, lam, D
+
+
+def qcriterion(u):
+    """Q [n][n][n] of a velocity field u [3][n][n][n] (Gauss-I4 derivatives)."""
+    u = _f64(u)
+    G = [grad(u[i]) for i in range(3)]          # G[i][j] = d_j u_i
+    Q = np.zeros_like(u[0])
+    for i in range(3):
+        for j in range(3):
+            Q -= 0.5 * G[i][j] * G[j][i]
+    return Q
 
 
 # ---------------------------------------------------------------- conv net

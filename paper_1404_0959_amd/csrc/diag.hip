@@ -1,0 +1,342 @@
+// diag.hip -- diagnostics of the velocity field on gfx950: the energy
+// spectrum and the Taylor micro-scale (through a radix-2 Stockham FFT done in
+// LDS, one line per LDS row), and the second invariant Q of the velocity
+// gradient.  These are the paper's validation quantities of the flow (Results
+// section: energy spectrum, Taylor micro-scale; third figure: Q iso-surfaces).
+//
+// Spectrum: u_hat(k) = DFT(u)(k) / n^3 over integer wavevectors with
+// components in [-n/2, n/2); shell s gathers the k with s - 1/2 <= |k| <
+// s + 1/2, E(s) = sum over the shell of |u_hat|^2 / 2, so sum_s E(s) =
+// <|u|^2>/2.  Taylor micro-scale lambda = sqrt(5 sum E / D) with D = sum_k
+// |k|^2 |u_hat(k)|^2 / 2.  Every sum runs in a fixed order (bitwise
+// reproducible): per z-plane of wavevectors and shell, then over planes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <new>
+
+#include "../../include/pisoc.h"
+#include "device.hpp"
+
+namespace pisoc {
+namespace {
+
+using cplx = double2;
+
+constexpr int kFftThreads = 256;
+constexpr int kFftLds = 2048;        // complex values per LDS buffer (two buffers)
+constexpr int kBinChunk = 2048;      // cells per LDS chunk of the shell binning
+constexpr int kMaxOwned = 4;         // shells per thread: bins <= 4 * 256
+
+bool pow2(int n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0; }
+int ilog2(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+// lines per FFT block: the two LDS buffers hold L lines of n complex values
+int fft_lines(int n) {
+    int L = kFftLds / n;
+    return L > n ? n : (L < 1 ? 1 : L);
+}
+
+// Shell of an integer |k|^2: s with s - 1/2 <= sqrt(k2) < s + 1/2, in integers
+// ((s + 1/2)^2 <= k2 <=> k2 >= s^2 + s + 1 for integer k2).
+__host__ __device__ inline int shell_of(int64_t k2) {
+    int64_t s = (int64_t)sqrt((double)k2);
+    while (s * s > k2) --s;
+    while ((s + 1) * (s + 1) <= k2) ++s;
+    return (int)(s + (k2 >= s * s + s + 1 ? 1 : 0));
+}
+
+// One FFT pass along axis AX (0 x, 1 y, 2 z) of the n^3 complex field f, in
+// place: block b loads L whole lines into LDS, runs log2(n) radix-2 Stockham
+// stages (stage with sub-transforms of size Ns: y[2(j - k) + k] = a + w b,
+// y[2(j - k) + k + Ns] = a - w b, a = x[j], b = x[j + n/2], k = j mod Ns,
+// w = exp(-i pi k / Ns)) and writes the lines back in natural order.  Along
+// x the lines are rows (contiguous); along y and z a block takes L lines at
+// consecutive x, so that each element's loads are L consecutive values.
+// With re (pass x only) the input is the real field re, imaginary part 0.
+template <int AX>
+__global__ void __launch_bounds__(kFftThreads) k_fft_axis(cplx* f, const double* re, int n,
+                                                         int logn, int L) {
+    extern __shared__ cplx lds_fft[];
+    cplx* A = lds_fft;
+    cplx* B = lds_fft + L * n;
+    const int tid = threadIdx.x;
+    const size_t nn = (size_t)n * n;
+    const int first = blockIdx.x * L;          // first line of the block
+    auto addr = [&](int l, int e) -> size_t {
+        if (AX == 0) {
+            const int idx = first + l, j = idx % n, k = idx / n;
+            return (size_t)e + (size_t)n * j + nn * k;
+        }
+        const int i0 = first % n, o = first / n;   // o: z (AX = 1) or y (AX = 2)
+        if (AX == 1) return (size_t)(i0 + l) + (size_t)n * e + nn * o;
+        return (size_t)(i0 + l) + (size_t)n * o + nn * e;
+    };
+    for (int t = tid; t < L * n; t += kFftThreads) {
+        const int l = AX == 0 ? t / n : t % L;
+        const int e = AX == 0 ? t % n : t / L;
+        const size_t a = addr(l, e);
+        A[l * n + e] = re ? cplx{re[a], 0.0} : f[a];
+    }
+    __syncthreads();
+    const int half = n >> 1;
+    for (int s = 0, Ns = 1; s < logn; ++s, Ns <<= 1) {
+        for (int t = tid; t < L * half; t += kFftThreads) {
+            const int l = t / half, j = t - l * half;
+            const int k = j & (Ns - 1);
+            double sn, cs;
+            sincospi(-(double)k / (double)Ns, &sn, &cs);
+            const cplx a = A[l * n + j], x = A[l * n + j + half];
+            const cplx wb = {x.x * cs - x.y * sn, x.x * sn + x.y * cs};
+            const int base = l * n + 2 * (j - k) + k;
+            B[base] = {a.x + wb.x, a.y + wb.y};
+            B[base + Ns] = {a.x - wb.x, a.y - wb.y};
+        }
+        __syncthreads();
+        cplx* t = A;
+        A = B;
+        B = t;
+    }
+    for (int t = tid; t < L * n; t += kFftThreads) {
+        const int l = AX == 0 ? t / n : t % L;
+        const int e = AX == 0 ? t % n : t / L;
+        f[addr(l, e)] = A[l * n + e];
+    }
+}
+
+// Signed wavenumber of DFT index i (components in [-n/2, n/2)).
+__device__ inline int wavenumber(int i, int n) { return i < n / 2 ? i : i - n; }
+
+// Shell binning of one component's transform f: block z (one plane of
+// wavevectors) adds e = |f|^2 / (2 n^6) of each of its cells to its shell.
+// The plane's cells pass through LDS in chunks; thread t owns the shells
+// s = t + 256 q and sums, in cell order, the entries of the chunk that fall
+// in them.  part[z * (bins + 1) + s] receives the plane's shell sums, and
+// part[z * (bins + 1) + bins] its sum of |k|^2 e (block reduction).
+__global__ void __launch_bounds__(kFftThreads) k_spectrum_bin(const cplx* f, int n, int bins,
+                                                            double inv_n6, double* part) {
+    __shared__ double ce[kBinChunk];
+    __shared__ int cs[kBinChunk];
+    __shared__ double red[16];
+    const int tid = threadIdx.x;
+    const int kz = wavenumber(blockIdx.x, n);
+    const size_t nn = (size_t)n * n;
+    const cplx* plane = f + nn * blockIdx.x;
+    double own[kMaxOwned] = {0.0, 0.0, 0.0, 0.0};
+    double dk = 0.0;
+    for (size_t c0 = 0; c0 < nn; c0 += kBinChunk) {
+        for (int t = tid; t < kBinChunk; t += kFftThreads) {
+            const size_t c = c0 + t;
+            if (c < nn) {
+                const int i = (int)(c % n), j = (int)(c / n);
+                const int kx = wavenumber(i, n), ky = wavenumber(j, n);
+                const int64_t k2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
+                const cplx v = plane[c];
+                const double e = 0.5 * (v.x * v.x + v.y * v.y) * inv_n6;
+                ce[t] = e;
+                cs[t] = shell_of(k2);
+                dk += (double)k2 * e;
+            } else {
+                ce[t] = 0.0;
+                cs[t] = -1;
+            }
+        }
+        __syncthreads();
+        for (int t = 0; t < kBinChunk; ++t) {
+            const int s = cs[t];
+            if (s >= 0 && (s & (kFftThreads - 1)) == tid) {
+                const int q = s / kFftThreads;
+#pragma unroll
+                for (int r = 0; r < kMaxOwned; ++r)   // a select, not a dynamic register index
+                    if (r == q) own[r] += ce[t];
+            }
+        }
+        __syncthreads();
+    }
+    double* out = part + (size_t)blockIdx.x * (bins + 1);
+    for (int q = 0; q < kMaxOwned; ++q) {
+        const int s = tid + q * kFftThreads;
+        if (s < bins) out[s] = own[q];
+    }
+    double v[1] = {dk};
+    block_reduce<1, 0u>(v, red);
+    if (tid == 0) out[bins] = v[0];
+}
+
+// Totals over the planes (in plane order) and over the three components'
+// partial sets (in component order): out[s] = E(s), out[bins] = D.
+__global__ void __launch_bounds__(kFftThreads) k_spectrum_total(const double* part, int n,
+                                                              int bins, double* out) {
+    const size_t set = (size_t)n * (bins + 1);
+    for (int s = threadIdx.x; s <= bins; s += kFftThreads) {
+        double acc = 0.0;
+        for (int c = 0; c < 3; ++c)
+            for (int z = 0; z < n; ++z) acc += part[c * set + (size_t)z * (bins + 1) + s];
+        out[s] = acc;
+    }
+}
+
+// Q = -(1/2) sum_ij (d_j u_i)(d_i u_j) per cell with the Gauss-I4 cell
+// derivative d_j q = (I4(q)_{P+1/2 e_j} - I4(q)_{P-1/2 e_j}) / h; partial sums
+// of Q and of (d_i u_i)^2 (the discrete identity sum Q = -(1/2) sum (div u)^2
+// holds for these antisymmetric, commuting difference operators).
+__global__ void __launch_bounds__(kBlock) k_qcrit(int n, double inv_h, const double* __restrict__ u,
+                                                  double* __restrict__ q, double* part) {
+    const size_t N = (size_t)n * n * n;
+    double v[2] = {0.0, 0.0};
+    for (size_t P = (size_t)blockIdx.x * blockDim.x + threadIdx.x; P < N;
+         P += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(P % n), j = (int)((P / n) % n), k = (int)(P / ((size_t)n * n));
+        const CellIdx c(n, i, j, k, 0);
+        double G[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double g[13];
+            gather13(u + a * N, c, g);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) G[a][b] = dgauss13(g, b, inv_h);
+        }
+        double Q = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) Q -= 0.5 * G[a][b] * G[b][a];
+        q[P] = Q;
+        const double div = G[0][0] + G[1][1] + G[2][2];
+        v[0] += Q;
+        v[1] += div * div;
+    }
+    block_partials<2, 0u>(v, part);
+}
+
+__global__ void __launch_bounds__(kBlock) k_qcrit_total(const double* part, unsigned nb,
+                                                        double* out) {
+    double t[2];
+    reduce_partials<2, 0u>(part, nb, t);
+    if (flat_tid() == 0) {
+        out[0] = t[0];
+        out[1] = t[1];
+    }
+}
+
+constexpr unsigned kQBlocks = 2048;
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Workspace: complex field, per-component plane partials, totals.
+struct DiagLayout {
+    size_t field, part, total_out, qpart, bytes;
+};
+DiagLayout diag_layout(int n) {
+    DiagLayout d{};
+    const size_t N = (size_t)n * n * n;
+    const int bins = shell_of(3LL * (n / 2) * (n / 2)) + 1;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off = align256(off + b);
+        return o;
+    };
+    d.field = take(sizeof(cplx) * N);
+    d.part = take(sizeof(double) * 3 * (size_t)n * (bins + 1));
+    d.total_out = take(sizeof(double) * (bins + 1));
+    d.qpart = take(sizeof(double) * 2 * kQBlocks + 16);
+    d.bytes = off;
+    return d;
+}
+
+}  // namespace
+}  // namespace pisoc
+
+using namespace pisoc;
+
+extern "C" {
+
+int32_t pisoc_diag_spectrum_bins(int32_t n) {
+    if (!pow2(n)) return 0;
+    return shell_of(3LL * (n / 2) * (n / 2)) + 1;
+}
+
+size_t pisoc_diag_workspace_bytes(int32_t n) {
+    if (n < PISOC_MIN_N || n > PISOC_MAX_N) return 0;
+    return diag_layout(n).bytes;
+}
+
+pisoc_status pisoc_diag_spectrum(int32_t n, const double* d_u, double* h_E, int32_t nbins,
+                                 double* h_taylor, double* h_dsum, void* d_ws, size_t ws_bytes,
+                                 void* hip_stream) {
+    if (!pow2(n) || !d_u || !h_E || nbins != pisoc_diag_spectrum_bins(n)) return PISOC_ERR_INVALID;
+    const DiagLayout Ly = diag_layout(n);
+    if (!d_ws || ws_bytes < Ly.bytes || (reinterpret_cast<uintptr_t>(d_ws) % 256) != 0)
+        return PISOC_ERR_WORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    char* ws = reinterpret_cast<char*>(d_ws);
+    cplx* f = reinterpret_cast<cplx*>(ws + Ly.field);
+    double* part = reinterpret_cast<double*>(ws + Ly.part);
+    double* tot = reinterpret_cast<double*>(ws + Ly.total_out);
+    const size_t N = (size_t)n * n * n;
+    const int L = fft_lines(n), logn = ilog2(n);
+    const unsigned blocks = (unsigned)((size_t)n * n / L);
+    const size_t lds = 2 * sizeof(cplx) * (size_t)L * n;
+    const double inv_n6 = 1.0 / ((double)N * (double)N);
+    const size_t set = (size_t)n * (nbins + 1);
+    for (int c = 0; c < 3; ++c) {
+        hipLaunchKernelGGL(k_fft_axis<0>, dim3(blocks), dim3(kFftThreads), lds, s, f, d_u + c * N,
+                           n, logn, L);
+        hipLaunchKernelGGL(k_fft_axis<1>, dim3(blocks), dim3(kFftThreads), lds, s, f, nullptr, n,
+                           logn, L);
+        hipLaunchKernelGGL(k_fft_axis<2>, dim3(blocks), dim3(kFftThreads), lds, s, f, nullptr, n,
+                           logn, L);
+        hipLaunchKernelGGL(k_spectrum_bin, dim3(n), dim3(kFftThreads), 0, s, f, n, nbins, inv_n6,
+                           part + c * set);
+    }
+    hipLaunchKernelGGL(k_spectrum_total, dim3(1), dim3(kFftThreads), 0, s, part, n, nbins, tot);
+    if (hipGetLastError() != hipSuccess) return PISOC_ERR_HIP;
+    // the totals come back through pageable memory after the stream has drained
+    if (hipStreamSynchronize(s) != hipSuccess) return PISOC_ERR_HIP;
+    double* host = new (std::nothrow) double[nbins + 1];
+    if (!host) return PISOC_ERR_INVALID;
+    const bool ok = hipMemcpy(host, tot, sizeof(double) * (nbins + 1), hipMemcpyDeviceToHost) ==
+                    hipSuccess;
+    if (ok) {
+        double e = 0.0;
+        for (int b = 0; b < nbins; ++b) {
+            h_E[b] = host[b];
+            e += host[b];
+        }
+        const double D = host[nbins];
+        if (h_taylor) *h_taylor = D > 0.0 ? std::sqrt(5.0 * e / D) : 0.0;
+        if (h_dsum) *h_dsum = D;
+    }
+    delete[] host;
+    return ok ? PISOC_OK : PISOC_ERR_HIP;
+}
+
+pisoc_status pisoc_diag_qcrit(int32_t n, const double* d_u, double* d_q, double* h_means,
+                              void* d_ws, size_t ws_bytes, void* hip_stream) {
+    if (n < PISOC_MIN_N || n > PISOC_MAX_N || !d_u || !d_q) return PISOC_ERR_INVALID;
+    const DiagLayout Ly = diag_layout(n);
+    if (!d_ws || ws_bytes < Ly.bytes || (reinterpret_cast<uintptr_t>(d_ws) % 256) != 0)
+        return PISOC_ERR_WORKSPACE;
+    const size_t N = (size_t)n * n * n;
+    double* qpart = reinterpret_cast<double*>(reinterpret_cast<char*>(d_ws) + Ly.qpart);
+    double* out = qpart + 2 * kQBlocks;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const double inv_h = (double)n / 6.283185307179586476925286766559;
+    hipLaunchKernelGGL(k_qcrit, dim3(kQBlocks), dim3(kBlock), 0, s, n, inv_h, d_u, d_q, qpart);
+    if (!h_means) return hipGetLastError() == hipSuccess ? PISOC_OK : PISOC_ERR_HIP;
+    hipLaunchKernelGGL(k_qcrit_total, dim3(1), dim3(kBlock), 0, s, qpart, kQBlocks, out);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return PISOC_ERR_HIP;
+    double t[2];
+    if (hipMemcpy(t, out, sizeof(t), hipMemcpyDeviceToHost) != hipSuccess) return PISOC_ERR_HIP;
+    h_means[0] = t[0] / (double)N;
+    h_means[1] = t[1] / (double)N;
+    return PISOC_OK;
+}
+
+}  // extern "C"

@@ -39,6 +39,8 @@ EXPORTED = [
     "pisoc_ens_workspace_bytes", "pisoc_ens_init", "pisoc_ens_step", "pisoc_ens_fields",
     "pisoc_ens_get_stats", "pisoc_ens_time", "pisoc_ens_steps_done", "pisoc_ens_num_classes",
     "pisoc_ens_class_info", "pisoc_ens_autotune", "pisoc_ens_destroy", "pisoc_ens_last_error",
+    "pisoc_diag_spectrum_bins", "pisoc_diag_workspace_bytes", "pisoc_diag_spectrum",
+    "pisoc_diag_qcrit",
 ]
 ENS_EAGER, ENS_GRAPH = 0, 1
 NET_NWEIGHTS = 15120
@@ -177,6 +179,15 @@ def lib():
     L.pisoc_ens_destroy.restype = None
     L.pisoc_ens_last_error.argtypes = [vp]
     L.pisoc_ens_last_error.restype = C.c_char_p
+    L.pisoc_diag_spectrum_bins.argtypes = [i32]
+    L.pisoc_diag_spectrum_bins.restype = i32
+    L.pisoc_diag_workspace_bytes.argtypes = [i32]
+    L.pisoc_diag_workspace_bytes.restype = sz
+    L.pisoc_diag_spectrum.argtypes = [i32, vp, C.POINTER(f64), i32, C.POINTER(f64),
+                                      C.POINTER(f64), vp, sz, vp]
+    L.pisoc_diag_spectrum.restype = C.c_int
+    L.pisoc_diag_qcrit.argtypes = [i32, vp, vp, C.POINTER(f64), vp, sz, vp]
+    L.pisoc_diag_qcrit.restype = C.c_int
     _lib = L
     return L
 
@@ -577,3 +588,38 @@ def helm_solve_noalloc(psidt, w, b, x0=None, tol=1e-10, maxit=1000, stream=None)
     if st < 0:
         raise PisocError(st, "pisoc_helm_solve_noalloc")
     return x, it.value, rel.value, st
+
+
+def spectrum(u, stream=None):
+    """Energy spectrum of a velocity field u (FP64 device tensor [3, n, n, n]):
+    (E per shell as a numpy array, Taylor micro-scale, D = sum |k|^2 |u_hat|^2 / 2)."""
+    import numpy as np
+    torch = _torch()
+    n = u.shape[-1]
+    bins = lib().pisoc_diag_spectrum_bins(n)
+    if bins == 0:
+        raise PisocError(ERR_INVALID, "spectrum needs n a power of two in 8..1024")
+    nbytes = lib().pisoc_diag_workspace_bytes(n)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=u.device)
+    E = (C.c_double * bins)()
+    lam, D = C.c_double(0.0), C.c_double(0.0)
+    st = lib().pisoc_diag_spectrum(n, u.data_ptr(), E, bins, C.byref(lam), C.byref(D),
+                                   ws.data_ptr(), nbytes, _stream_ptr(torch, stream))
+    if st != OK:
+        raise PisocError(st, "pisoc_diag_spectrum")
+    return np.array(E[:]), lam.value, D.value
+
+
+def qcriterion(u, stream=None):
+    """Q of a velocity field u (FP64 device tensor [3, n, n, n]): (Q tensor, <Q>, <(div u)^2>)."""
+    torch = _torch()
+    n = u.shape[-1]
+    nbytes = lib().pisoc_diag_workspace_bytes(n)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=u.device)
+    q = torch.empty(u.shape[1:], dtype=torch.float64, device=u.device)
+    means = (C.c_double * 2)()
+    st = lib().pisoc_diag_qcrit(n, u.data_ptr(), q.data_ptr(), means, ws.data_ptr(), nbytes,
+                                _stream_ptr(torch, stream))
+    if st != OK:
+        raise PisocError(st, "pisoc_diag_qcrit")
+    return q, means[0], means[1]
