@@ -399,6 +399,15 @@ pisoc_status pisoc_diag_spectrum(int32_t n, const double* d_u, double* h_E, int3
  * <(div u)^2> (Gauss-I4), then the call synchronises; else asynchronous. */
 pisoc_status pisoc_diag_qcrit(int32_t n, const double* d_u, double* d_q, double* h_means,
                               void* d_ws, size_t ws_bytes, void* hip_stream);
+/* Filtered (a-priori sub-grid) statistics, the use the Results section plans
+ * for the DNS data base: with the separable top-hat filter of width 2h
+ * (weights 1/4, 1/2, 1/4 along each axis; transfer prod_d (1 + cos k_d h)/2),
+ * u_bar = bar(u), tau_ij = bar(u_i u_j) - u_bar_i u_bar_j,
+ * S_bar_ij = (d_j u_bar_i + d_i u_bar_j)/2 (Gauss-I4), Pi = -tau_ij S_bar_ij:
+ * h_out[4] (host) = <|u_bar|^2>/2, <tau_ii/2>, <Pi>, fraction of cells with
+ * Pi < 0 (backscatter).  Synchronises. */
+pisoc_status pisoc_diag_sgs(int32_t n, const double* d_u, double* h_out, void* d_ws,
+                            size_t ws_bytes, void* hip_stream);
 
 /* ---- learned initial guess of the pressure correction --------------------
  * Not in the paper: a small network predicts the start of each pressure solve

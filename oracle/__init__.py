@@ -227,7 +227,12 @@ def guess_start(psidt, K, b, g):
 #    (the isotropic relation lambda^2 = 15 nu u'^2 / eps with u'^2 = (2/3) int E
 #    and eps = 2 nu int k^2 E), with |k|^2 of each wavevector, not of its shell;
 #  * Q = (|Omega|^2 - |S|^2)/2 = -(1/2) sum_ij (d_j u_i)(d_i u_j) per cell, with
-#    the Gauss-I4 cell derivatives of the enstrophy statistic.
+#    the Gauss-I4 cell derivatives of the enstrophy statistic;
+#  * filtered (a-priori sub-grid) statistics, the DNS data base's second use
+#    named in the Results section: the separable top-hat of width 2h with
+#    weights (1/4, 1/2, 1/4), the sub-grid stress tau_ij = bar(u_i u_j) -
+#    u_bar_i u_bar_j, its energy k_sgs = tau_ii/2 and the energy flux
+#    Pi = -tau_ij S_bar_ij to the sub-grid scales.
 
 
 def spectrum_bins(n):
@@ -273,6 +278,37 @@ def qcriterion(u):
         for j in range(3):
             Q -= 0.5 * G[i][j] * G[j][i]
     return Q
+
+
+def box_filter(q):
+    """Separable discrete top-hat of width 2h: weights (1/4, 1/2, 1/4) along each
+    axis (transfer function prod_d (1 + cos k_d h) / 2), periodic."""
+    q = _f64(q)
+    out = q
+    for ax in (0, 1, 2):
+        out = 0.25 * np.roll(out, 1, axis=ax) + 0.5 * out + 0.25 * np.roll(out, -1, axis=ax)
+    return out
+
+
+def sgs_stats(u):
+    """A-priori statistics of the filter box_filter applied to u [3][n][n][n]:
+    (<|u_bar|^2>/2, <k_sgs>, <Pi>, fraction of cells with Pi < 0), where
+    tau_ij = bar(u_i u_j) - u_bar_i u_bar_j, k_sgs = tau_ii / 2,
+    S_bar_ij = (d_j u_bar_i + d_i u_bar_j) / 2 (Gauss-I4) and Pi = -tau_ij S_bar_ij.
+    Also returns the per-cell k_sgs and Pi fields."""
+    u = _f64(u)
+    ub = [box_filter(u[i]) for i in range(3)]
+    G = [grad(ub[i]) for i in range(3)]          # G[i][j] = d_j ubar_i
+    ksgs = np.zeros_like(u[0])
+    Pi = np.zeros_like(u[0])
+    for i in range(3):
+        for j in range(3):
+            tau = box_filter(u[i] * u[j]) - ub[i] * ub[j]
+            if i == j:
+                ksgs += 0.5 * tau
+            Pi -= tau * 0.5 * (G[i][j] + G[j][i])
+    res = float(np.mean(0.5 * (ub[0] ** 2 + ub[1] ** 2 + ub[2] ** 2)))
+    return (res, float(np.mean(ksgs)), float(np.mean(Pi)), float(np.mean(Pi < 0.0))), ksgs, Pi
 
 
 # ---------------------------------------------------------------- conv net

@@ -4,6 +4,10 @@
 // gradient.  These are the paper's validation quantities of the flow (Results
 // section: energy spectrum, Taylor micro-scale; third figure: Q iso-surfaces).
 //
+// Filtered statistics: the separable top-hat of width 2h (weights 1/4, 1/2,
+// 1/4 per axis), the sub-grid stress, its energy and the energy flux to the
+// sub-grid scales (the a-priori tests the paper plans for its DNS data base).
+//
 // Spectrum: u_hat(k) = DFT(u)(k) / n^3 over integer wavevectors with
 // components in [-n/2, n/2); shell s gathers the k with s - 1/2 <= |k| <
 // s + 1/2, E(s) = sum over the shell of |u_hat|^2 / 2, so sum_s E(s) =
@@ -223,6 +227,88 @@ __global__ void __launch_bounds__(kBlock) k_qcrit_total(const double* part, unsi
     }
 }
 
+// Filtered (a-priori sub-grid) statistics: the separable top-hat of width 2h
+// (weights 1/4, 1/2, 1/4 along each axis) of u_i and of u_i u_j, into nine
+// fields F (u_bar x, y, z; bar(u u) xx, xy, xz, yy, yz, zz).
+__global__ void __launch_bounds__(kBlock) k_sgs_filter(int n, const double* __restrict__ u,
+                                                       double* __restrict__ F) {
+    const size_t N = (size_t)n * n * n;
+    for (size_t P = (size_t)blockIdx.x * blockDim.x + threadIdx.x; P < N;
+         P += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(P % n), j = (int)((P / n) % n), k = (int)(P / ((size_t)n * n));
+        const CellIdx c(n, i, j, k, 0);
+        double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const double w = (dx ? 0.25 : 0.5) * (dy ? 0.25 : 0.5) * (dz ? 0.25 : 0.5);
+                    const size_t Q = c.self() + (size_t)(ptrdiff_t)(c.off[0][dx + 2] +
+                                                                    c.off[1][dy + 2] +
+                                                                    c.off[2][dz + 2]);
+                    const double a = u[Q], b = u[N + Q], e = u[2 * N + Q];
+                    acc[0] += w * a;
+                    acc[1] += w * b;
+                    acc[2] += w * e;
+                    acc[3] += w * a * a;
+                    acc[4] += w * a * b;
+                    acc[5] += w * a * e;
+                    acc[6] += w * b * b;
+                    acc[7] += w * b * e;
+                    acc[8] += w * e * e;
+                }
+#pragma unroll
+        for (int f = 0; f < 9; ++f) F[f * N + P] = acc[f];
+    }
+}
+
+// Per cell tau_ij = bar(u_i u_j) - u_bar_i u_bar_j, k_sgs = tau_ii / 2,
+// S_bar_ij = (d_j u_bar_i + d_i u_bar_j) / 2 (Gauss-I4), Pi = -tau_ij S_bar_ij;
+// partial sums of |u_bar|^2 / 2, k_sgs, Pi and of the cells with Pi < 0.
+__global__ void __launch_bounds__(kBlock) k_sgs_stats(int n, double inv_h,
+                                                      const double* __restrict__ F,
+                                                      double* part) {
+    const size_t N = (size_t)n * n * n;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (size_t P = (size_t)blockIdx.x * blockDim.x + threadIdx.x; P < N;
+         P += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(P % n), j = (int)((P / n) % n), k = (int)(P / ((size_t)n * n));
+        const CellIdx c(n, i, j, k, 0);
+        double G[3][3], ub[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double g[13];
+            gather13(F + a * N, c, g);
+            ub[a] = g[0];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) G[a][b] = dgauss13(g, b, inv_h);
+        }
+        // bar(u u) in the order xx, xy, xz, yy, yz, zz
+        const int slot[3][3] = {{3, 4, 5}, {4, 6, 7}, {5, 7, 8}};
+        double ks = 0.0, pi = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const double tau = F[slot[a][b] * N + P] - ub[a] * ub[b];
+                if (a == b) ks += 0.5 * tau;
+                pi -= tau * 0.5 * (G[a][b] + G[b][a]);
+            }
+        v[0] += 0.5 * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
+        v[1] += ks;
+        v[2] += pi;
+        v[3] += pi < 0.0 ? 1.0 : 0.0;
+    }
+    block_partials<4, 0u>(v, part);
+}
+
+__global__ void __launch_bounds__(kBlock) k_sgs_total(const double* part, unsigned nb,
+                                                      double* out) {
+    double t[4];
+    reduce_partials<4, 0u>(part, nb, t);
+    if (flat_tid() == 0)
+        for (int c = 0; c < 4; ++c) out[c] = t[c];
+}
+
 constexpr unsigned kQBlocks = 2048;
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -241,10 +327,11 @@ DiagLayout diag_layout(int n) {
         off = align256(off + b);
         return o;
     };
-    d.field = take(sizeof(cplx) * N);
+    // the spectrum's complex field or the nine filtered fields (never both at once)
+    d.field = take(sizeof(double) * 9 * N);
     d.part = take(sizeof(double) * 3 * (size_t)n * (bins + 1));
     d.total_out = take(sizeof(double) * (bins + 1));
-    d.qpart = take(sizeof(double) * 2 * kQBlocks + 16);
+    d.qpart = take(sizeof(double) * (4 * kQBlocks + 16));
     d.bytes = off;
     return d;
 }
@@ -336,6 +423,30 @@ pisoc_status pisoc_diag_qcrit(int32_t n, const double* d_u, double* d_q, double*
     if (hipMemcpy(t, out, sizeof(t), hipMemcpyDeviceToHost) != hipSuccess) return PISOC_ERR_HIP;
     h_means[0] = t[0] / (double)N;
     h_means[1] = t[1] / (double)N;
+    return PISOC_OK;
+}
+
+pisoc_status pisoc_diag_sgs(int32_t n, const double* d_u, double* h_out, void* d_ws,
+                            size_t ws_bytes, void* hip_stream) {
+    if (n < PISOC_MIN_N || n > PISOC_MAX_N || !d_u || !h_out) return PISOC_ERR_INVALID;
+    const DiagLayout Ly = diag_layout(n);
+    if (!d_ws || ws_bytes < Ly.bytes || (reinterpret_cast<uintptr_t>(d_ws) % 256) != 0)
+        return PISOC_ERR_WORKSPACE;
+    const size_t N = (size_t)n * n * n;
+    char* ws = reinterpret_cast<char*>(d_ws);
+    double* F = reinterpret_cast<double*>(ws + Ly.field);
+    double* part = reinterpret_cast<double*>(ws + Ly.qpart);
+    double* out = part + 4 * kQBlocks;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const double inv_h = (double)n / 6.283185307179586476925286766559;
+    hipLaunchKernelGGL(k_sgs_filter, dim3(kQBlocks), dim3(kBlock), 0, s, n, d_u, F);
+    hipLaunchKernelGGL(k_sgs_stats, dim3(kQBlocks), dim3(kBlock), 0, s, n, inv_h, F, part);
+    hipLaunchKernelGGL(k_sgs_total, dim3(1), dim3(kBlock), 0, s, part, kQBlocks, out);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return PISOC_ERR_HIP;
+    double t[4];
+    if (hipMemcpy(t, out, sizeof(t), hipMemcpyDeviceToHost) != hipSuccess) return PISOC_ERR_HIP;
+    for (int c = 0; c < 4; ++c) h_out[c] = t[c] / (double)N;
     return PISOC_OK;
 }
 

@@ -40,7 +40,7 @@ EXPORTED = [
     "pisoc_ens_get_stats", "pisoc_ens_time", "pisoc_ens_steps_done", "pisoc_ens_num_classes",
     "pisoc_ens_class_info", "pisoc_ens_autotune", "pisoc_ens_destroy", "pisoc_ens_last_error",
     "pisoc_diag_spectrum_bins", "pisoc_diag_workspace_bytes", "pisoc_diag_spectrum",
-    "pisoc_diag_qcrit",
+    "pisoc_diag_qcrit", "pisoc_diag_sgs",
 ]
 ENS_EAGER, ENS_GRAPH = 0, 1
 NET_NWEIGHTS = 15120
@@ -188,6 +188,8 @@ def lib():
     L.pisoc_diag_spectrum.restype = C.c_int
     L.pisoc_diag_qcrit.argtypes = [i32, vp, vp, C.POINTER(f64), vp, sz, vp]
     L.pisoc_diag_qcrit.restype = C.c_int
+    L.pisoc_diag_sgs.argtypes = [i32, vp, C.POINTER(f64), vp, sz, vp]
+    L.pisoc_diag_sgs.restype = C.c_int
     _lib = L
     return L
 
@@ -623,3 +625,18 @@ def qcriterion(u, stream=None):
     if st != OK:
         raise PisocError(st, "pisoc_diag_qcrit")
     return q, means[0], means[1]
+
+
+def sgs_stats(u, stream=None):
+    """Filtered statistics of a velocity field u (FP64 device tensor [3, n, n, n]):
+    (<|u_bar|^2>/2, <k_sgs>, <Pi>, fraction of cells with Pi < 0)."""
+    torch = _torch()
+    n = u.shape[-1]
+    nbytes = lib().pisoc_diag_workspace_bytes(n)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=u.device)
+    out = (C.c_double * 4)()
+    st = lib().pisoc_diag_sgs(n, u.data_ptr(), out, ws.data_ptr(), nbytes,
+                              _stream_ptr(torch, stream))
+    if st != OK:
+        raise PisocError(st, "pisoc_diag_sgs")
+    return tuple(out)

@@ -89,3 +89,16 @@ def test_spectrum_rejects_unsupported_sizes(P):
     u = torch.zeros((3, 40, 40, 40), dtype=torch.float64, device="cuda")
     with pytest.raises(P.PisocError):
         P.spectrum(u)
+
+
+@pytest.mark.parametrize("n", [16, 40, 64])
+def test_sgs_stats_vs_oracle(P, ora, n):
+    u = make_hit_case(n, 7, mach=0.5).u
+    got = P.sgs_stats(dev(u))
+    want, _, _ = ora.sgs_stats(u)
+    print(f"filtered statistics {n}^3: gpu {got}, oracle {want}")
+    for g, w in zip(got[:3], want[:3]):
+        assert abs(g - w) <= 1e-12 * abs(w)
+    # the backscatter fraction counts cells; a cell with Pi within rounding of
+    # 0 could fall either side, so one cell's worth of slack
+    assert abs(got[3] - want[3]) <= 1.0 / n ** 3 + 1e-15

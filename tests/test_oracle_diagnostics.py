@@ -77,3 +77,45 @@ def test_q_sum_identity(ora):
     Q = ora.qcriterion(u)
     div = ora.div_vel(u)
     assert abs(Q.sum() + 0.5 * np.sum(div * div)) < 1e-12 * np.sum(div * div)
+
+
+# ------------------------------------------------------------ filtered statistics
+def test_box_filter_transfer_function(ora):
+    """A Fourier mode comes out of the filter multiplied by
+    prod_d (1 + cos k_d h) / 2, which fixes the weights (1/4, 1/2, 1/4)."""
+    n = 16
+    h, (x, y, z) = grid(n)
+    k = (1, 3, 2)
+    q = np.cos(k[0] * x + k[1] * y + k[2] * z + 0.4)
+    T = np.prod([(1 + math.cos(kd * h)) / 2 for kd in k])
+    assert np.max(np.abs(ora.box_filter(q) - T * q)) < 1e-14
+    assert np.max(np.abs(ora.box_filter(np.full((n, n, n), 2.5)) - 2.5)) < 1e-15
+
+
+def test_sgs_galilean_and_positive(ora):
+    """tau is unchanged by a uniform velocity added to the field, and k_sgs >= 0
+    in every cell (the filter's weights are positive and sum to 1)."""
+    u = make_hit_case(16, 6, mach=0.2).u
+    (r1, k1, p1, f1), ks1, pi1 = ora.sgs_stats(u)
+    shift = np.array([0.7, -1.2, 0.4])[:, None, None, None]
+    (r2, k2, p2, f2), ks2, pi2 = ora.sgs_stats(u + shift)
+    assert np.max(np.abs(ks1 - ks2)) < 1e-12 * np.max(ks1)
+    assert np.max(np.abs(pi1 - pi2)) < 1e-11 * np.max(np.abs(pi1))
+    assert ks1.min() >= -1e-15
+    assert 0.0 < f1 < 1.0
+
+
+def test_sgs_single_shear_mode(ora):
+    """u = (0, A sin kx, 0): tau_yy = (A^2/2) [(1 - T1^2) - (T2 - T1^2) cos 2kx],
+    T_m = (1 + cos m k h)/2, tau_xy = 0 and S_bar_yy = 0, so Pi = 0: a single
+    shear mode transfers no energy."""
+    n, A, k = 32, 0.8, 3
+    h, (x, y, z) = grid(n)
+    u = np.stack([np.zeros_like(x), A * np.sin(k * x), np.zeros_like(x)])
+    (res, ks, pi, frac), ksf, pif = ora.sgs_stats(u)
+    T1 = (1 + math.cos(k * h)) / 2
+    T2 = (1 + math.cos(2 * k * h)) / 2
+    want = 0.25 * A * A * ((1 - T1 * T1) - (T2 - T1 * T1) * np.cos(2 * k * x))
+    assert np.max(np.abs(ksf - want)) < 1e-15
+    assert np.max(np.abs(pif)) < 1e-15
+    assert abs(res - 0.25 * A * A * T1 * T1) < 1e-15
