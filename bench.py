@@ -147,12 +147,22 @@ def ensemble_run(P, torch, args, weights):
     t0 = time.perf_counter()
     E.autotune(cache, force=True)
     out["autotune_s"] = round(time.perf_counter() - t0, 3)
-    E.step(args.warmup, mode=P.ENS_GRAPH)
     st_holder = {}
 
-    def graph_steps(k):
-        st_holder["st"], st_holder["info"] = E.step(k, mode=P.ENS_GRAPH)
-    el = timed(graph_steps, args.ens_steps)
+    def graph_steps(mode):
+        def run(k):
+            st_holder["st"], st_holder["info"] = E.step(k, mode=mode)
+        return run
+    # one graph per size class, replayed on the class streams
+    E.step(args.warmup, mode=P.ENS_GRAPH)
+    el = timed(graph_steps(P.ENS_GRAPH), args.ens_steps)
+    out["per_class_graphs"] = dict(value=cells * args.ens_steps / el,
+                                   ms_per_step=el * 1e3 / args.ens_steps)
+    log(f"ensemble, one graph per class: {el * 1e3 / args.ens_steps:.3f} ms/step")
+    # one graph for the whole ensemble: one launch per step (the value)
+    E.step(args.warmup, mode=P.ENS_GRAPH_ONE)
+    el = timed(graph_steps(P.ENS_GRAPH_ONE), args.ens_steps)
+    out["mode"] = "one graph launch per step (every size class a branch)"
     out["value"] = cells * args.ens_steps / el
     out["unit"] = "cell-steps/s"
     out["ms_per_step"] = el * 1e3 / args.ens_steps
@@ -162,7 +172,8 @@ def ensemble_run(P, torch, args, weights):
     out["classes"] = [{k: c[k] for k in ("n", "members", "block", "cells_z", "cg_cells_z",
                                          "tiled_cells_z", "caps", "rounds", "guess_mask")}
                       for c in E.classes()]
-    log(f"ensemble graph: {out['ms_per_step']:.3f} ms/step, {out['value']:.4e} cell-steps/s")
+    log(f"ensemble, one graph per step: {out['ms_per_step']:.3f} ms/step, "
+        f"{out['value']:.4e} cell-steps/s")
 
     def eager_steps(k):
         E.step(k, mode=P.ENS_EAGER)

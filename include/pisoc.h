@@ -262,7 +262,12 @@ int32_t pisoc_profile_read(const pisoc_ctx* ctx, pisoc_kernel_stat* h_out, int32
  * rolled back in this mode (PISOC_ERR_DIVERGED after the fact). */
 typedef struct pisoc_ens pisoc_ens;
 
-enum { PISOC_ENS_EAGER = 0, PISOC_ENS_GRAPH = 1 };
+/* PISOC_ENS_GRAPH_ONE is PISOC_ENS_GRAPH with one graph for the whole ensemble:
+ * every size class's step is a branch of it (forked from and joined into the
+ * first class's stream), so a step is one graph launch.  Calls of the two
+ * captured modes may alternate; each drops the other's graphs and captures
+ * its own (after one eager step). */
+enum { PISOC_ENS_EAGER = 0, PISOC_ENS_GRAPH = 1, PISOC_ENS_GRAPH_ONE = 2 };
 
 typedef struct {
     int32_t n, members;                 /* grid size, members of the class */

@@ -1538,6 +1538,11 @@ struct pisoc_ens {
     std::vector<hipStream_t> streams;             // one per class
     // captured step of each class (replayed on its own stream), per buffer parity
     std::vector<std::array<hipGraphExec_t, 2>> exec;
+    // or, in one_graph mode, one graph holding every class's step as a branch
+    // (forked from and joined into the first class's stream), per parity
+    std::array<hipGraphExec_t, 2> one{nullptr, nullptr};
+    bool one_graph = false;        // which kind the built graphs are
+    std::vector<hipEvent_t> fork_join;   // [0]: fork; [c]: join of class c
     int parity = 0;
     bool built = false;
     int64_t steps = 0;
@@ -1553,6 +1558,11 @@ void drop_graphs(pisoc_ens* e) {
                 (void)hipGraphExecDestroy(g);
                 g = nullptr;
             }
+    for (auto& g : e->one)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
     e->built = false;
 }
 
@@ -1567,10 +1577,77 @@ void set_caps(pisoc_ctx* ctx, const int* first, int later, int rounds) {
     ctx->rounds = std::max(ctx->rounds, std::max(1, std::min(rounds + 1, ctx->prm.max_refine)));
 }
 
+// One graph per parity holding every class's step: the capture begins on the
+// first class's stream, the other class streams join it through a fork event
+// and are joined back before it ends, so each class is a branch of the graph.
+pisoc_status build_one_graph(pisoc_ens* e) {
+    drop_graphs(e);
+    for (pisoc_ctx* ctx : e->cls)
+        if (audit_on(ctx)) audit_decide_capture(ctx);
+    const size_t C = e->cls.size();
+    if (e->fork_join.size() != C) {
+        for (hipEvent_t ev : e->fork_join) (void)hipEventDestroy(ev);
+        e->fork_join.assign(C, nullptr);
+        for (size_t c = 0; c < C; ++c)
+            if (hipEventCreateWithFlags(&e->fork_join[c], hipEventDisableTiming) != hipSuccess) {
+                e->err = "hipEventCreate failed";
+                return PISOC_ERR_HIP;
+            }
+    }
+    hipStream_t origin = e->cls[0]->stream;
+    auto fail = [&](int par, pisoc_status st, const std::string& why) {
+        e->err = why;
+        if (par == 1)
+            for (pisoc_ctx* ctx : e->cls) rotate(ctx);
+        drop_graphs(e);
+        return st;
+    };
+    for (int par = 0; par < 2; ++par) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(par, PISOC_ERR_HIP, "hipStreamBeginCapture failed");
+        bool ok = hipEventRecord(e->fork_join[0], origin) == hipSuccess;
+        for (size_t c = 1; c < C && ok; ++c)
+            ok = hipStreamWaitEvent(e->cls[c]->stream, e->fork_join[0], 0) == hipSuccess;
+        pisoc_status st = PISOC_OK;
+        for (size_t c = 0; c < C && ok && st == PISOC_OK; ++c) {
+            pisoc_ctx* ctx = e->cls[c];
+            st = ctx->prm.precision == PISOC_FP64 ? enqueue_step<double>(ctx, false)
+                                                  : enqueue_step<float>(ctx, false);
+            if (st != PISOC_OK) e->err = ctx->err;
+        }
+        for (size_t c = 1; c < C && ok; ++c)
+            ok = hipEventRecord(e->fork_join[c], e->cls[c]->stream) == hipSuccess &&
+                 hipStreamWaitEvent(origin, e->fork_join[c], 0) == hipSuccess;
+        const hipError_t rc_end = hipStreamEndCapture(origin, &g);
+        if (!ok || st != PISOC_OK || rc_end != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(par, st != PISOC_OK ? st : PISOC_ERR_HIP,
+                        std::string("graph capture failed: ") +
+                            (st != PISOC_OK ? e->err : std::string(hipGetErrorString(rc_end))));
+        }
+        const hipError_t rc = hipGraphInstantiate(&e->one[par], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (rc != hipSuccess) {
+            e->one[par] = nullptr;
+            return fail(par, PISOC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(rc));
+        }
+        for (pisoc_ctx* ctx : e->cls) rotate(ctx);
+    }
+    for (pisoc_ctx* ctx : e->cls) {
+        std::copy(ctx->caps, ctx->caps + PISOC_MAX_CORR, ctx->caps_built);
+        ctx->cap_later_built = ctx->cap_later;
+    }
+    e->built = true;
+    e->one_graph = true;
+    e->parity = 0;
+    return PISOC_OK;
+}
+
 // Capture one step of each class on its own stream into exec[c][0], then,
 // with the buffers rotated, into exec[c][1]; rotations restored.  The classes
 // are independent graphs so that their replays on the class streams overlap.
-pisoc_status build_graphs(pisoc_ens* e) {
+pisoc_status build_class_graphs(pisoc_ens* e) {
     drop_graphs(e);
     e->exec.assign(e->cls.size(), {nullptr, nullptr});
     for (pisoc_ctx* ctx : e->cls)
@@ -1613,8 +1690,15 @@ pisoc_status build_graphs(pisoc_ens* e) {
         ctx->cap_later_built = ctx->cap_later;
     }
     e->built = true;
+    e->one_graph = false;
     e->parity = 0;
     return PISOC_OK;
+}
+
+// The graphs of the kind a captured mode replays (mode PISOC_ENS_GRAPH: one per
+// class; PISOC_ENS_GRAPH_ONE: one for the whole ensemble).
+pisoc_status build_graphs(pisoc_ens* e, bool one) {
+    return one ? build_one_graph(e) : build_class_graphs(e);
 }
 
 bool same_class_params(const pisoc_params& a, const pisoc_params& b) {
@@ -1846,18 +1930,22 @@ pisoc_status pisoc_ens_init(const pisoc_params* members, int32_t count, void* d_
 }
 
 pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_step_info* h_info) {
-    if (!e || n_steps < 0 || (mode != PISOC_ENS_EAGER && mode != PISOC_ENS_GRAPH))
+    if (!e || n_steps < 0 ||
+        (mode != PISOC_ENS_EAGER && mode != PISOC_ENS_GRAPH && mode != PISOC_ENS_GRAPH_ONE))
         return PISOC_ERR_INVALID;
     if (n_steps == 0) return PISOC_OK;
     pisoc_status worst = PISOC_OK;
     std::vector<pisoc_step_info> rec(e->count);
+    const bool one = mode == PISOC_ENS_GRAPH_ONE;
+    // graphs of the other captured kind are dropped; this call captures its own
+    if (mode != PISOC_ENS_EAGER && e->built && e->one_graph != one) drop_graphs(e);
     if (mode == PISOC_ENS_EAGER || !e->built) {
         // eager steps.  A captured call begins with one, which measures the CG
         // iterations that size the graph's caps, or with two where the
         // learned-guess audit has yet to measure both of its choices (the
         // capture takes its verdict); the graph is built once that is done.
         int k = n_steps;
-        if (mode == PISOC_ENS_GRAPH) {
+        if (mode != PISOC_ENS_EAGER) {
             int need = 1;
             for (pisoc_ctx* ctx : e->cls)
                 if (audit_on(ctx) && !audit_measured(ctx))
@@ -1912,7 +2000,7 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
             if (h_info) std::copy(rec.begin(), rec.end(), h_info);
             return worst;
         }
-        pisoc_status st = build_graphs(e);
+        pisoc_status st = build_graphs(e, one);
         if (st != PISOC_OK) {
             // the eager steps of this call stand; their records go out with the error
             if (h_info) std::copy(rec.begin(), rec.end(), h_info);
@@ -1923,8 +2011,26 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
         // each class's graph runs on the class stream, after the work already
         // there (set-up, eager steps, copies)
         for (pisoc_ctx* ctx : e->cls) clear_acc(ctx->stream, ctx->st, ctx->batch);
+        if (e->one_graph) {
+            // the whole-ensemble graph runs on the first class's stream, after
+            // the work already on every class stream
+            hipStream_t origin = e->cls[0]->stream;
+            for (size_t c = 1; c < e->cls.size(); ++c)
+                if (hipEventRecord(e->fork_join[c], e->cls[c]->stream) != hipSuccess ||
+                    hipStreamWaitEvent(origin, e->fork_join[c], 0) != hipSuccess) {
+                    e->err = "hipEventRecord/hipStreamWaitEvent failed";
+                    return PISOC_ERR_HIP;
+                }
+        }
         for (int i = 0; i < n_steps; ++i) {
-            for (size_t c = 0; c < e->cls.size(); ++c) {
+            if (e->one_graph) {
+                const hipError_t rc = hipGraphLaunch(e->one[e->parity], e->cls[0]->stream);
+                if (rc != hipSuccess) {
+                    e->err = std::string("hipGraphLaunch: ") + hipGetErrorString(rc);
+                    return PISOC_ERR_HIP;
+                }
+            }
+            for (size_t c = 0; c < e->cls.size() && !e->one_graph; ++c) {
                 const hipError_t rc = hipGraphLaunch(e->exec[c][e->parity], e->cls[c]->stream);
                 if (rc != hipSuccess) {
                     e->err = std::string("hipGraphLaunch: ") + hipGetErrorString(rc);
@@ -1937,6 +2043,18 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
                 ctx->steps += 1;
             }
             e->steps += 1;
+        }
+        if (e->one_graph) {
+            // every class stream waits for the graphs on the first class's
+            // stream before its own next work (the state read-back below first)
+            hipStream_t origin = e->cls[0]->stream;
+            bool ok = hipEventRecord(e->fork_join[0], origin) == hipSuccess;
+            for (size_t c = 1; c < e->cls.size() && ok; ++c)
+                ok = hipStreamWaitEvent(e->cls[c]->stream, e->fork_join[0], 0) == hipSuccess;
+            if (!ok) {
+                e->err = "hipEventRecord/hipStreamWaitEvent failed";
+                return PISOC_ERR_HIP;
+            }
         }
         pisoc_status st = ens_sync(e);
         if (st != PISOC_OK) return st;
@@ -1985,7 +2103,7 @@ pisoc_status pisoc_ens_step(pisoc_ens* e, int32_t n_steps, int32_t mode, pisoc_s
         }
         if ((regrow_any || near_any) && !bad && !bad_dt) {
             // a capture needs no eager step here: the caps are known
-            pisoc_status bs = build_graphs(e);
+            pisoc_status bs = build_graphs(e, e->one_graph);
             if (bs != PISOC_OK) {
                 // the steps of this call stand; their records go out with the error
                 if (h_info) std::copy(rec.begin(), rec.end(), h_info);
@@ -2094,6 +2212,7 @@ void pisoc_ens_destroy(pisoc_ens* e) {
     for (pisoc_ctx* ctx : e->cls)
         if (ctx && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     drop_graphs(e);
+    for (hipEvent_t ev : e->fork_join) (void)hipEventDestroy(ev);
     for (pisoc_ctx* ctx : e->cls) free_ctx(ctx);
     for (hipStream_t s : e->streams) (void)hipStreamDestroy(s);
     delete e;

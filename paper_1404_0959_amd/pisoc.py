@@ -42,7 +42,7 @@ EXPORTED = [
     "pisoc_diag_spectrum_bins", "pisoc_diag_workspace_bytes", "pisoc_diag_spectrum",
     "pisoc_diag_qcrit", "pisoc_diag_sgs",
 ]
-ENS_EAGER, ENS_GRAPH = 0, 1
+ENS_EAGER, ENS_GRAPH, ENS_GRAPH_ONE = 0, 1, 2
 NET_NWEIGHTS = 15120
 NET_CH = (2, 16, 16, 16, 1)
 

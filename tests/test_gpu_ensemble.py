@@ -366,3 +366,50 @@ def test_captured_solve_at_cap_reports_its_residual(P, ora):
           f"caps {[c['caps'][:2] for c in ens.classes()]}")
     assert hit, "the caps were not reached: the test does not exercise the cap"
     assert abs(true_rel / reported - 1) < 1e-2
+
+
+def test_one_graph_per_step_fp64(P):
+    """PISOC_ENS_GRAPH_ONE: the whole ensemble's step is one graph launch (each
+    size class a branch); FP64 steps are bitwise those of the per-class graphs
+    and of eager steps, and the captured modes may alternate on one ensemble."""
+    cs = cases()
+    kw = dict(p_tol=1e-9)
+    a = P.Ensemble(cs, **kw)
+    b = P.Ensemble(cs, **kw)
+    c = P.Ensemble(cs, **kw)
+    for _ in range(6):
+        sa, ia = a.step(1, mode=P.ENS_EAGER)
+    sb, ib = b.step(6, mode=P.ENS_GRAPH_ONE)
+    for nst, mode in ((2, P.ENS_GRAPH_ONE), (2, P.ENS_GRAPH), (1, P.ENS_EAGER),
+                      (1, P.ENS_GRAPH_ONE)):
+        sc, ic = c.step(nst, mode=mode)
+        assert sc in (P.OK, P.WARN_DUST)
+    assert sa == sb and sa in (P.OK, P.WARN_DUST)
+    assert b.steps_done == c.steps_done == 6
+    for m in range(len(cs)):
+        assert ia[m]["pcg_iters"] == ib[m]["pcg_iters"] == ic[m]["pcg_iters"], m
+        fa = fields(P, lambda bits: a.fields(m, bits))
+        fb = fields(P, lambda bits: b.fields(m, bits))
+        fc = fields(P, lambda bits: c.fields(m, bits))
+        for k in fa:
+            assert np.array_equal(fa[k], fb[k]) and np.array_equal(fa[k], fc[k]), (m, k)
+
+
+def test_one_graph_benchmark_ensemble(P):
+    """The benchmark's 64 mixed members (FP32 + learned guess, audited) in
+    one-graph mode: every solve meets the tolerance, gas mass is conserved."""
+    from paper_1404_0959_amd.learn import load_weights
+    w = load_weights()
+    cs = ensemble_cases(64, seed=0)
+    E = P.Ensemble(cs, p_tol=1e-6, precision=P.FP32_REFINED, inner_tol=1e-6,
+                   guess=P.GUESS_LEARNED, guess_weights=w.data_ptr(), guess_audit=16)
+    m0 = [s["mass_gas"] for s in E.stats()]
+    E.step(1, mode=P.ENS_EAGER)
+    E.autotune()
+    st, info = E.step(10, mode=P.ENS_GRAPH_ONE)
+    assert st in (P.OK, P.WARN_DUST, P.WARN_GUESS_FALLBACK)
+    eps32 = float(np.finfo(np.float32).eps)
+    for m, i in enumerate(info):
+        assert max(i["pcg_relres"]) <= 1e-6, (m, i)
+        # FP64 sums of FP32-stored densities: a random walk of FP32 roundings
+        assert abs(i["mass_gas"] / m0[m] - 1) <= 8 * eps32 * np.sqrt(11 / cs[m].n ** 3)
