@@ -44,6 +44,7 @@ class OraParams(C.Structure):
         ("dt_max", C.c_double),
         ("n_corr", C.c_int32), ("n_mom_sweeps", C.c_int32), ("n_dust_sweeps", C.c_int32),
         ("p_tol", C.c_double), ("p_maxit", C.c_int32),
+        ("two_way", C.c_int32), ("gravity", C.c_double * 3),
     ]
 
 
@@ -356,7 +357,8 @@ class Oracle:
 
     def __init__(self, n, rho, u, rho_p=None, *, gamma=1.4, C_=None, mu=1e-3, tau_p=(),
                  cfl=0.5, dt_growth=1.2, dt_fixed=0.0, dt_max=0.0, n_corr=2, n_mom_sweeps=4,
-                 n_dust_sweeps=4, p_tol=1e-8, p_maxit=500, capture=False):
+                 n_dust_sweeps=4, p_tol=1e-8, p_maxit=500, capture=False, two_way=False,
+                 gravity=(0.0, 0.0, 0.0)):
         if C_ is None:
             raise ValueError("closure constant C_ is required")
         tau_p = tuple(tau_p)
@@ -369,6 +371,9 @@ class Oracle:
         prm.cfl, prm.dt_growth, prm.dt_fixed, prm.dt_max = cfl, dt_growth, dt_fixed, dt_max
         prm.n_corr, prm.n_mom_sweeps, prm.n_dust_sweeps = n_corr, n_mom_sweeps, n_dust_sweeps
         prm.p_tol, prm.p_maxit = p_tol, p_maxit
+        prm.two_way = 1 if two_way else 0
+        for d in range(3):
+            prm.gravity[d] = gravity[d]
         self.prm = prm
         self.n = n
         self.K = len(tau_p)

@@ -320,6 +320,8 @@ struct ora_state {
     double* u[3];
     double* phi[3];
     double* rho_p[ORA_MAX_CLASSES];
+    /* two-way: the dust mass fluxes of the last step, summed over the classes */
+    double* fd[3];
     /* captured pressure systems of the last step, one set per corrector */
     double* sys_b[ORA_MAX_CORR];
     double* sys_w[ORA_MAX_CORR];
@@ -357,6 +359,7 @@ static void free_state(ora_state* s) {
     for (int d = 0; d < 3; ++d) {
         free(s->u[d]);
         free(s->phi[d]);
+        free(s->fd[d]);
     }
     for (int c = 0; c < ORA_MAX_CLASSES; ++c) free(s->rho_p[c]);
     for (int c = 0; c < ORA_MAX_CORR; ++c) {
@@ -375,17 +378,28 @@ static void free_state(ora_state* s) {
 
 int ora_num_threads(void) { return omp_get_max_threads(); }
 
-/* Initial mass fluxes: phi_d = I4(rho) I4(u_d) A on every face. */
+/* Initial mass fluxes: phi_d = I4(rho) I4(u_d) A on every face; with two-way
+ * coupling also the dust's, fd_d = I4(sum_j rho_j) I4(u_d) A (the dust moving
+ * with the gas: its drift needs Du/Dt, unknown before the first step). */
 static void initial_fluxes(ora_state* s) {
     double* fr = alloc_field(s->N);
     double* fu = alloc_field(s->N);
+    double* rd = alloc_field(s->N);
+    for (int c = 0; c < s->p.n_classes; ++c)
+        for (size_t P = 0; P < s->N; ++P) rd[P] += s->rho_p[c][P];
     for (int d = 0; d < 3; ++d) {
         ora_i4(s->n, d, s->rho, fr);
         ora_i4(s->n, d, s->u[d], fu);
         for (size_t P = 0; P < s->N; ++P) s->phi[d][P] = fr[P] * fu[P] * s->A;
+        if (s->p.two_way) {
+            s->fd[d] = alloc_field(s->N);
+            ora_i4(s->n, d, rd, fr);
+            for (size_t P = 0; P < s->N; ++P) s->fd[d][P] = fr[P] * fu[P] * s->A;
+        }
     }
     free(fr);
     free(fu);
+    free(rd);
 }
 
 int ora_create(const ora_params* prm, const double* rho, const double* u, const double* rho_p,
@@ -496,10 +510,43 @@ static int one_step(ora_state* s, ora_info* info) {
     ora_div_flux(n, s->phi[0], s->phi[1], s->phi[2], divphi);
     for (size_t P = 0; P < N; ++P) rhos[P] = s->rho[P] - dt * divphi[P];
 
+    /* ---- two-way coupling: the momentum equation is the mixture's.  Its
+     * density rho_m = rho + rho_d (rho_d = sum_j rho_j), predicted as
+     * rho_m* = rho_m^n - dt div(F_m^n), convected by the mixture mass flux
+     * F_m = phi + fd (fd: the dust's mass fluxes of the last step), with the
+     * buoyancy (rho_m^n - <rho_m^n>) g.  One-way: rho_m = rho, F_m = phi. ---- */
+    double* fm[3] = {s->phi[0], s->phi[1], s->phi[2]};
+    double* divfm = divphi;
+    double* rms = rhos;             /* predicted density of the momentum equation */
+    double* rmn = s->rho;           /* its density at t^n */
+    double mean_m = 0.0;
+    if (pr->two_way) {
+        NEWF(rdn);
+        memset(rdn, 0, N * sizeof(double));   /* pool arrays keep the last step's values */
+        for (int c = 0; c < pr->n_classes; ++c)
+            for (size_t P = 0; P < N; ++P) rdn[P] += s->rho_p[c][P];
+        NEWF(fm0); NEWF(fm1); NEWF(fm2);
+        fm[0] = fm0; fm[1] = fm1; fm[2] = fm2;
+        for (int d = 0; d < 3; ++d)
+            for (size_t P = 0; P < N; ++P) fm[d][P] = s->phi[d][P] + s->fd[d][P];
+        NEWF(dfm);
+        divfm = dfm;
+        ora_div_flux(n, fm[0], fm[1], fm[2], divfm);
+        NEWF(rmn_);
+        NEWF(rms_);
+        rmn = rmn_;
+        rms = rms_;
+        for (size_t P = 0; P < N; ++P) {
+            rmn[P] = s->rho[P] + rdn[P];
+            rms[P] = rmn[P] - dt * divfm[P];
+        }
+        mean_m = sum_field(n, rmn) / (double)N;
+    }
+
     /* ---- 3. momentum coefficients and explicit source ---- */
     NEWF(aP);
     for (size_t P = 0; P < N; ++P)
-        aP[P] = rhos[P] / dt + (9.0 / 16.0) * divphi[P] + 6.0 * mu / (h * h);
+        aP[P] = rms[P] / dt + (9.0 / 16.0) * divfm[P] + 6.0 * mu / (h * h);
     NEWF(divu);
     NEWF(gd0); NEWF(gd1); NEWF(gd2);
     double* gdivu[3] = {gd0, gd1, gd2};
@@ -508,8 +555,10 @@ static int one_step(ora_state* s, ora_info* info) {
     NEWF(s0); NEWF(s1); NEWF(s2);
     double* src[3] = {s0, s1, s2};
     for (int d = 0; d < 3; ++d)
-        for (size_t P = 0; P < N; ++P)
-            src[d][P] = s->rho[P] * s->u[d][P] / dt + (mu / 3.0) * gdivu[d][P];
+        for (size_t P = 0; P < N; ++P) {
+            src[d][P] = rmn[P] * s->u[d][P] / dt + (mu / 3.0) * gdivu[d][P];
+            if (pr->two_way) src[d][P] += (rmn[P] - mean_m) * pr->gravity[d];
+        }
     NEWF(pn);
     for (size_t P = 0; P < N; ++P) pn[P] = Cc * pow(s->rho[P], g);
     NEWF(gp0); NEWF(gp1); NEWF(gp2);
@@ -531,7 +580,7 @@ static int one_step(ora_state* s, ora_info* info) {
     }
     for (int sweep = 0; sweep < pr->n_mom_sweeps; ++sweep) {
         for (int d = 0; d < 3; ++d) {
-            mom_offdiag(s, s->phi, divphi, ucur[d], noff, tface, tlap);
+            mom_offdiag(s, fm, divfm, ucur[d], noff, tface, tlap);
             for (size_t P = 0; P < N; ++P)
                 unew[d][P] = (src[d][P] - noff[P] - gpn[d][P]) / aP[P];
         }
@@ -569,7 +618,7 @@ static int one_step(ora_state* s, ora_info* info) {
         }
         /* 5.2 HbyA = H(u)/a_P with H(u) = s - N(u) */
         for (int d = 0; d < 3; ++d) {
-            mom_offdiag(s, s->phi, divphi, ucur[d], noff, tface, tlap);
+            mom_offdiag(s, fm, divfm, ucur[d], noff, tface, tlap);
             for (size_t P = 0; P < N; ++P) hbya[d][P] = (src[d][P] - noff[P]) / aP[P];
         }
         /* 5.3-5.5 predicted fluxes, face coefficients, continuity defect */
@@ -623,6 +672,7 @@ static int one_step(ora_state* s, ora_info* info) {
     }
 
     /* ---- 7. Equilibrium-Eulerian dust, one class at a time ---- */
+    int fd_slot = -1;
     double* rpn[ORA_MAX_CLASSES] = {0};
     if (pr->n_classes > 0) {
         /* particle-velocity correction source: a = Du/Dt, backward-Euler time
@@ -640,13 +690,19 @@ static int one_step(ora_state* s, ora_info* info) {
                 for (int e = 0; e < 3; ++e) conv += ucur[e][P] * gu[d][e][P];
                 acc[d][P] = (ucur[d][P] - s->u[d][P]) / dt + conv;
             }
-        /* class-independent face factor D_d = I4(rho^{n+1}) I4(a_d) A */
+        /* class-independent face factor D_d = I4(rho^{n+1}) (I4(a_d) - g_d) A:
+         * the drift u_j - u = tau_j (g - Du/Dt) at the faces */
         double* Dfa[3];
         for (int d = 0; d < 3; ++d) {
             Dfa[d] = pool_get(s, slot++);
             ora_i4(n, d, rhok, ir);
             ora_i4(n, d, acc[d], ih);
-            for (size_t P = 0; P < N; ++P) Dfa[d][P] = ir[P] * ih[P] * A;
+            for (size_t P = 0; P < N; ++P) Dfa[d][P] = ir[P] * (ih[P] - pr->gravity[d]) * A;
+        }
+        double* fdn[3] = {NULL, NULL, NULL};   /* two-way: the dust mass fluxes of this step */
+        if (pr->two_way) {
+            fd_slot = slot;
+            for (int d = 0; d < 3; ++d) fdn[d] = pool_get(s, slot++);
         }
         NEWF(G0); NEWF(G1); NEWF(G2);
         double* G[3] = {G0, G1, G2};
@@ -681,6 +737,9 @@ static int one_step(ora_state* s, ora_info* info) {
             for (int d = 0; d < 3; ++d) {
                 ora_i4(n, d, Y, tface[d]);
                 for (size_t P = 0; P < N; ++P) tface[d][P] *= G[d][P];
+                if (pr->two_way)
+                    for (size_t P = 0; P < N; ++P)
+                        fdn[d][P] = (c == 0 ? 0.0 : fdn[d][P]) + tface[d][P];
             }
             ora_div_flux(n, tface[0], tface[1], tface[2], ry);
             rpn[c] = pool_get(s, slot++);
@@ -719,6 +778,9 @@ static int one_step(ora_state* s, ora_info* info) {
             memcpy(s->rho_p[c], rpn[c], N * sizeof(double));
             info->mass_p[c] = sum_field(n, s->rho_p[c]) * V;
         }
+        if (pr->two_way && fd_slot >= 0)
+            for (int d = 0; d < 3; ++d)
+                memcpy(s->fd[d], pool_get(s, fd_slot + d), N * sizeof(double));
         s->t += dt;
         s->dt_prev = dt;
     }

@@ -53,6 +53,12 @@ typedef struct {
     int32_t n_corr, n_mom_sweeps, n_dust_sweeps;
     double p_tol;
     int32_t p_maxit;
+    /* two-way coupling: the gas momentum is the mixture's (density rho + sum rho_j,
+     * convected by the gas plus dust mass fluxes, buoyancy (rho_m - <rho_m>) g) */
+    int32_t two_way;
+    /* gravity: the dust settles with u_j = u + tau_j (g - Du/Dt); with two_way
+     * the mixture also feels its buoyancy */
+    double gravity[3];
 } ora_params;
 
 typedef struct {
