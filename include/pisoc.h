@@ -120,6 +120,15 @@ typedef struct {
                                   that went without it).  Eager ensemble steps audit the
                                   same way; a captured ensemble step keeps the verdict
                                   its graph was built with (without the periodic trial) */
+    int32_t two_way;           /* != 0: two-way coupling.  The momentum equation is the
+                                  mixture's: density rho_m = rho + sum_j rho_j, convected by
+                                  the gas plus dust mass fluxes (the dust's of the last
+                                  step), with the buoyancy (rho_m - <rho_m>) gravity; the
+                                  pressure stays the gas's C rho^gamma (Introduction:
+                                  buoyancy of the gas-particle mixture; Results: Marble's
+                                  dusty gas, third footnote) */
+    double gravity[3];         /* g: the dust settles with u_j = u + tau_j (g - Du/Dt); with
+                                  two_way the mixture also feels its buoyancy */
 } pisoc_params;
 
 typedef struct {

@@ -28,6 +28,7 @@ struct Phys {
     size_t N, NT;       // cells per member, cells of all members
     double h, inv_h, inv_h2, V, inv_V, A;
     double gamma, C, mu;
+    double g[3];        // gravity (settling drift; with two-way coupling also buoyancy)
 };
 
 // State of one pressure solve, kept on the device so that CG never returns to
@@ -72,6 +73,9 @@ struct DevState {
     int32_t steps_acc;
     int32_t it_first_max[kMaxCorr];
     int32_t it_later_max[kMaxCorr];
+    // two-way coupling: mean mixture density <rho + sum_j rho_j> (a constant of
+    // the run: gas and dust masses are conserved exactly)
+    double rhom_mean;
 };
 
 // A cell and the periodic offsets to the cells up to two steps away along

@@ -75,6 +75,31 @@ __global__ void __launch_bounds__(kBlock) k_init_phi(Phys ph, const DevState* st
     END_CELLS
 }
 
+// Two-way coupling, initial dust mass fluxes fd_d = I4(sum_j rho_j) I4(u_d) A
+// (the dust moving with the gas: its drift needs Du/Dt, unknown before the
+// first step).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_init_fd(Phys ph, int ncls, const T* __restrict__ rhoj,
+                                                    const T* __restrict__ u, T* __restrict__ fd) {
+    MEMBER(ph)
+    const size_t N = ncell(ph);
+    const T A = (T)ph.A;
+    FOR_CELLS(ph)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        T q[4];
+#pragma unroll
+        for (int s = -1; s <= 2; ++s) {
+            T acc = T(0);
+            for (int j = 0; j < ncls; ++j) acc += rhoj[j * N + c.sh(d, s)];
+            q[s + 1] = acc;
+        }
+        const T rd = (T(9) * (q[1] + q[2]) - (q[0] + q[3])) * T(0.0625);
+        fd[d * N + P] = rd * i4(u + d * N, c, d, 0) * A;
+    }
+    END_CELLS
+}
+
 // ---------------------------------------------------------------- time step
 // Convective Courant rate sigma_P = sum_f |phi_f| / (2 rho_P V) of a cell
 // from its own (fp) and lower (fm) face fluxes and its density deviation r.
@@ -212,6 +237,44 @@ __global__ void __launch_bounds__(kBlock) k_mom_source(Phys ph, const DevState* 
     mom_source_cell(dv, uv, rho, dt, m3, inv_h, out);
 #pragma unroll
     for (int m = 0; m < 3; ++m) s[m * N + P] = out[m];
+    END_CELLS
+}
+
+// Two-way coupling: the momentum equation becomes the mixture's, density
+// rho_m = rho + rho_d (rho_d = sum_j rho_j) convected by the mixture mass flux
+// F_m = phi + F_d (F_d: the dust mass fluxes of the last step).  From the gas
+// predictor's a_P and source: a_P += rho_d^n / dt - (7/16) div F_d, which makes
+// it rho_m*/dt + (9/16) div F_m + 6 mu/h^2 with rho_m* = rho_m^n - dt div F_m;
+// s += rho_d^n u^n / dt + (rho_m^n - <rho_m>) g; F_m is written for the
+// momentum sweeps and H/a_P.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_mixture(Phys ph, const DevState* st, int ncls,
+                                                    const T* __restrict__ rn,
+                                                    const T* __restrict__ un,
+                                                    const T* __restrict__ rhoj,
+                                                    const T* __restrict__ phi,
+                                                    const T* __restrict__ fd, T* __restrict__ fm,
+                                                    T* __restrict__ aP, T* __restrict__ src) {
+    MEMBER(ph)
+    const size_t N = ncell(ph);
+    const T dt = (T)(st + mem_)->dt, inv_V = (T)ph.inv_V;
+    const double rref = (st + mem_)->rho_ref, mean = (st + mem_)->rhom_mean;
+    FOR_CELLS(ph)
+    T rd = T(0);
+    for (int j = 0; j < ncls; ++j) rd += rhoj[j * N + P];
+    T dfd = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T fo = fd[d * N + P];
+        dfd += fo - fd[d * N + c.sh(d, -1)];
+        fm[d * N + P] = phi[d * N + P] + fo;
+    }
+    dfd *= inv_V;
+    aP[P] += rd / dt - T(0.4375) * dfd;
+    const double rm = rref + (double)rn[P] + (double)rd;
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+        src[m * N + P] += rd * un[m * N + P] / dt + (T)((rm - mean) * ph.g[m]);
     END_CELLS
 }
 
@@ -1806,13 +1869,15 @@ __global__ void __launch_bounds__(kBlock) k_dudt(Phys ph, const DevState* st,
 }
 
 // Particle mass flux per unit mass ratio on own faces,
-// G_d = phi_d - tau I4(rho^{n+1}) I4(a_d) A  (u_p = u - tau Du/Dt at the face),
-// and the starting mass ratio Y = rho_j^n / rho^n.
+// G_d = phi_d - tau I4(rho^{n+1}) (I4(a_d) - g_d) A  (u_p = u + tau (g - Du/Dt)
+// at the face), and the starting mass ratio Y = rho_j^n / rho^n.
 template <typename T>
 __device__ inline void dust_flux_cell(const T (&rv)[13], const T (&al)[3][5], const T (&fv)[3],
-                                      T rj, T rnP, T t, T rref, T A, T (&g)[3], T& y) {
+                                      T rj, T rnP, T t, T rref, T A, const double (&gr)[3],
+                                      T (&g)[3], T& y) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) g[d] = fv[d] - t * (rref + i4g(rv, d, 0)) * i4l<T>(al[d], 0) * A;
+    for (int d = 0; d < 3; ++d)
+        g[d] = fv[d] - t * (rref + i4g(rv, d, 0)) * (i4l<T>(al[d], 0) - (T)gr[d]) * A;
     y = rj / (rref + rnP);
 }
 
@@ -1835,7 +1900,7 @@ __global__ void __launch_bounds__(kBlock) k_dust_flux(Phys ph, const DevState* s
     const T rj = rhoj[P], rnP = rn[P];
     loads_issued();
     T g[3], y;
-    dust_flux_cell(rv, al, fv, rj, rnP, t, rref, A, g, y);
+    dust_flux_cell(rv, al, fv, rj, rnP, t, rref, A, ph.g, g, y);
 #pragma unroll
     for (int d = 0; d < 3; ++d) G[d * N + P] = g[d];
     Y[P] = y;
@@ -1904,11 +1969,14 @@ __global__ void __launch_bounds__(kBlock) k_dust_faceflux(Phys ph, const T* __re
 
 // Conservative finish rho_j^{n+1} = rho_j^n - dt div(F); partial sums of
 // rho_j^{n+1} (mass; non-finite if any value is) and max(-rho_j^{n+1}).
+// fdo (two-way coupling): the class's own-face fluxes are added to the
+// mixture's dust flux F_d of the next step (written by the first class).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dust_finish(Phys ph, const DevState* st,
                                                         const T* __restrict__ rhoj,
                                                         const T* __restrict__ F, T* __restrict__ rhoj1,
-                                                        double* partials) {
+                                                        double* partials, T* __restrict__ fdo,
+                                                        int first) {
     MEMBER(ph)
     const size_t N = ncell(ph);
     const T dt = (T)(st + mem_)->dt, inv_V = (T)ph.inv_V;
@@ -1917,6 +1985,9 @@ __global__ void __launch_bounds__(kBlock) k_dust_finish(Phys ph, const DevState*
     T dF = T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) dF += F[d * N + P] - F[d * N + c.sh(d, -1)];
+    if (fdo)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fdo[d * N + P] = (first ? T(0) : fdo[d * N + P]) + F[d * N + P];
     const T out = rhoj[P] - dt * dF * inv_V;
     rhoj1[P] = out;
     v[0] += (double)out;
@@ -2572,6 +2643,7 @@ struct TiledDustFlux : TiledBase<T> {
     const T *phi, *rhoj, *rn;
     T *G, *Y;
     T A, t, rref;
+    double gr[3];
     int cls;
     struct Pts { T f[3], rj, rn; };
     __device__ void member(const Phys& ph, const DevState* d) {
@@ -2579,6 +2651,9 @@ struct TiledDustFlux : TiledBase<T> {
         A = (T)ph.A;
         t = (T)d->tau[cls];
         rref = (T)d->rho_ref;
+        gr[0] = ph.g[0];
+        gr[1] = ph.g[1];
+        gr[2] = ph.g[2];
     }
     __device__ Pts load(size_t P) const {
         return {{stream_ld(phi + P), stream_ld(phi + this->NT + P),
@@ -2591,7 +2666,7 @@ struct TiledDustFlux : TiledBase<T> {
 #pragma unroll
         for (int d = 0; d < 3; ++d) cross_line(v[1 + d], d, al[d]);
         T g[3], y;
-        dust_flux_cell(v[0], al, p.f, p.rj, p.rn, t, rref, A, g, y);
+        dust_flux_cell(v[0], al, p.f, p.rj, p.rn, t, rref, A, gr, g, y);
 #pragma unroll
         for (int d = 0; d < 3; ++d) stream_st(G + (d * this->NT + P), g[d]);
         stream_st(Y + P, y);
@@ -2638,9 +2713,12 @@ struct TiledDustFinish : TiledBase<T> {
     const T* sf[1];
     const T* rhoj;
     T* rhoj1;
+    T* fdo;        // two-way coupling: the dust flux F_d of the next step (as k_dust_finish)
+    int first_cls;
     T dt, inv_V;
     struct Pts { T rj; };
     __device__ void member(const Phys& ph, const DevState* d) {
+        this->NT = ph.NT;
         dt = (T)d->dt;
         inv_V = (T)ph.inv_V;
     }
@@ -2654,6 +2732,12 @@ struct TiledDustFinish : TiledBase<T> {
         T dF = T(0);
 #pragma unroll
         for (int d = 0; d < 3; ++d) dF += fp[d] * i4g(v[0], d, 0) - fm[d] * i4g(v[0], d, -1);
+        if (fdo)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                T* q = fdo + (d * this->NT + P);
+                *q = (first_cls ? T(0) : *q) + fp[d] * i4g(v[0], d, 0);
+            }
         const T out = p.rj - dt * dF * inv_V;
         stream_st(rhoj1 + P, out);
         acc[0] += (double)out;
@@ -3166,8 +3250,19 @@ void Ops<T>::dust_faceflux(const Launch& L, hipStream_t s, const Phys& ph, const
 }
 template <typename T>
 void Ops<T>::dust_finish(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                         const T* rhoj, const T* F, T* rhoj1, double* part) {
-    LAUNCH(k_dust_finish<T>, L, s, ph, st, rhoj, F, rhoj1, part);
+                         const T* rhoj, const T* F, T* rhoj1, double* part, T* fdo, bool first) {
+    LAUNCH(k_dust_finish<T>, L, s, ph, st, rhoj, F, rhoj1, part, fdo, first ? 1 : 0);
+}
+template <typename T>
+void Ops<T>::init_fd(const Launch& L, hipStream_t s, const Phys& ph, int ncls, const T* rhoj,
+                     const T* u, T* fd) {
+    LAUNCH(k_init_fd<T>, L, s, ph, ncls, rhoj, u, fd);
+}
+template <typename T>
+void Ops<T>::mixture(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st, int ncls,
+                     const T* rn, const T* un, const T* rhoj, const T* phi, const T* fd, T* fm,
+                     T* aP, T* src) {
+    LAUNCH(k_mixture<T>, L, s, ph, st, ncls, rn, un, rhoj, phi, fd, fm, aP, src);
 }
 template <typename T, bool LAST>
 static unsigned corr_finish_tiled(const Launch& TL, hipStream_t s, const Phys& ph,
@@ -3203,13 +3298,15 @@ unsigned Ops<T>::corr_finish_fused(const Launch& TL, hipStream_t s, const Phys& 
 template <typename T>
 unsigned Ops<T>::dust_finish_fused(const Launch& TL, hipStream_t s, const Phys& ph,
                                    const DevState* st, const T* Y, const T* G, const T* rhoj,
-                                   T* rhoj1, double* part) {
+                                   T* rhoj1, double* part, T* fdo, bool first) {
     TiledDustFinish<T> k{};
     k.sf[0] = Y;
     k.face = G;
     k.part = part;
     k.rhoj = rhoj;
     k.rhoj1 = rhoj1;
+    k.fdo = fdo;
+    k.first_cls = first ? 1 : 0;
     return tiled_launch<T>(TL, s, ph, st, k);
 }
 template <typename T>

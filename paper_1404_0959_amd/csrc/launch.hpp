@@ -173,15 +173,26 @@ struct Ops {
                                const DevState* st, const T* Yin, T* Yout, const T* G,
                                const T* rhoj, const T* r1, double* part_diag);
     static void dust_faceflux(const Launch& L, hipStream_t s, const Phys& ph, const T* Y, T* G);
-    // partials: two columns of L.nblocks from part on, sum rho_j and max(-rho_j)
+    // partials: two columns of L.nblocks from part on, sum rho_j and max(-rho_j);
+    // fdo (two-way coupling, else null): the class's own-face fluxes go into the
+    // next step's dust flux F_d (written by the first class, added by the others)
     static void dust_finish(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                            const T* rhoj, const T* F, T* rhoj1, double* part);
+                            const T* rhoj, const T* F, T* rhoj1, double* part, T* fdo,
+                            bool first);
+    // two-way coupling: initial dust mass fluxes fd = I4(sum_j rho_j) I4(u) A
+    static void init_fd(const Launch& L, hipStream_t s, const Phys& ph, int ncls,
+                        const T* rhoj, const T* u, T* fd);
+    // two-way coupling: a_P and the source of the mixture, and its mass flux fm
+    static void mixture(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                        int ncls, const T* rn, const T* un, const T* rhoj, const T* phi,
+                        const T* fd, T* fm, T* aP, T* src);
     // dust_faceflux and dust_finish in one tiled pass (TL.nblocks > 0), F not
     // stored; returns the number of partials written per column (two columns,
     // as dust_finish)
     static unsigned dust_finish_fused(const Launch& TL, hipStream_t s, const Phys& ph,
                                       const DevState* st, const T* Y, const T* G,
-                                      const T* rhoj, T* rhoj1, double* part);
+                                      const T* rhoj, T* rhoj1, double* part, T* fdo,
+                                      bool first);
     static void stats_gas(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                           const T* r, const T* u, double* part);
     // st non-null: per-member (a, b) = st[m].aff

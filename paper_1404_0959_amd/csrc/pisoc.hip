@@ -66,6 +66,7 @@ struct Layout {
     size_t rn, rk, aP, divu, pn, w, p0, r, r2, x, diag, pp0, pp1, pp2, q, q2, Y0, Y1;
     size_t u3[3], phin, phik, src, hbya, phiH, acc, G;
     size_t rhop, rhop1;
+    size_t fd0, fd1, fm;   // two-way coupling: dust mass fluxes (two rotating), mixture flux
     // FP64 fields when capturing: b, diag, p0, p', w = rho/a_P (snapshot slots
     // 0-4), u* (5-7), and with the learned guess g and the solve start x0 (8, 9)
     size_t snap;
@@ -79,12 +80,13 @@ struct Layout {
 enum KCls {
     KC_CFL, KC_PREDICT, KC_MOM_SOURCE, KC_MOM_SWEEP, KC_HBYA, KC_CORR_RHS, KC_PCG_SPMV,
     KC_CORR_FLUX, KC_CORR_UPDATE, KC_DUDT, KC_DUST_FLUX, KC_DUST_SWEEP,
-    KC_DUST_FACEFLUX, KC_DUST_FINISH, KC_REFINE, KC_NET, KC_COUNT
+    KC_DUST_FACEFLUX, KC_DUST_FINISH, KC_REFINE, KC_NET, KC_MIXTURE, KC_COUNT
 };
 const char* const kKernelName[KC_COUNT] = {
     "k_cfl", "k_predict", "k_mom_source", "k_mom_sweep", "k_hbya", "k_corr_rhs",
     "k_pcg_spmv", "k_corr_flux", "k_corr_update", "k_dudt", "k_dust_flux",
-    "k_dust_sweep", "k_dust_faceflux", "k_dust_finish", "k_refine", "learned_guess"};
+    "k_dust_sweep", "k_dust_faceflux", "k_dust_finish", "k_refine", "learned_guess",
+    "k_mixture"};
 
 struct Prof {
     bool on = false;
@@ -175,6 +177,8 @@ bool valid_params(const pisoc_params* p, std::string* why) {
     if (p->guess == PISOC_GUESS_LEARNED && (!p->d_guess_weights || p->n % 16 != 0))
         return fail("learned guess needs d_guess_weights and n % 16 == 0");
     if (p->guess_audit < 0) return fail("guess_audit must be >= 0");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(p->gravity[d])) return fail("gravity must be finite");
     return true;
 }
 
@@ -203,6 +207,11 @@ Layout make_layout(const pisoc_params* p, int batch) {
     for (size_t* o : three) *o = take(3 * es * N);
     L.rhop = take(es * N * (size_t)std::max(p->n_classes, 1));
     L.rhop1 = take(es * N * (size_t)std::max(p->n_classes, 1));
+    if (p->two_way) {
+        L.fd0 = take(3 * es * N);
+        L.fd1 = take(3 * es * N);
+        L.fm = take(3 * es * N);
+    }
     L.snap = p->capture ? take((p->guess == PISOC_GUESS_LEARNED ? 10 : 8) * sizeof(double) * N)
                         : 0;
     if (p->guess == PISOC_GUESS_LEARNED) {
@@ -251,6 +260,7 @@ struct pisoc_ctx {
     int u_idx[3];   // which of lay.u3 holds u^n, work a, work b
     int ucur_slot;  // u_idx slot holding u* after the predictor sweeps (1 or 2)
     size_t rn, rk, phin, phik, rhop, rhop1;
+    size_t fdn, fdk;   // two-way coupling: dust mass fluxes of the last step / this one
     double t;
     int64_t steps;
     int pred_first[PISOC_MAX_CORR];  // CG iterations of the last first solve (all members)
@@ -343,6 +353,7 @@ Phys make_phys(const pisoc_params* p, const Launch& L, int batch) {
     ph.gamma = p->gamma;
     ph.C = p->C;
     ph.mu = p->mu;
+    for (int d = 0; d < 3; ++d) ph.g[d] = p->gravity[d];
     return ph;
 }
 
@@ -486,6 +497,9 @@ struct StepPtrs {
     T *rn, *rk, *un, *ua, *ub, *phin, *phik;
     T *aP, *divu, *pn, *src, *hb, *w, *p0, *phiH, *r, *r2, *x, *dg, *pp0, *pp1, *pp2, *q, *q2;
     T *acc, *G, *Ya, *Yb, *rj, *rj1;
+    // two-way coupling: dust fluxes of the last step and of this one, the
+    // mixture flux; mflux: the momentum equation's convecting flux (phin or fm)
+    T *fdn, *fdk, *fm, *mflux;
     double *snap, *b64, *x64a, *x64b;
     T* xf;   // FP32: the refinement's rounded solution (exchanged with x after a solve)
 };
@@ -525,6 +539,11 @@ StepPtrs<T> step_ptrs(const pisoc_ctx* ctx) {
     P.Yb = F(Y.Y1);
     P.rj = F(ctx->rhop);
     P.rj1 = F(ctx->rhop1);
+    const bool tw = ctx->prm.two_way != 0;
+    P.fdn = tw ? F(ctx->fdn) : nullptr;
+    P.fdk = tw ? F(ctx->fdk) : nullptr;
+    P.fm = tw ? F(Y.fm) : nullptr;
+    P.mflux = tw ? P.fm : P.phin;
     P.snap = ctx->prm.capture ? reinterpret_cast<double*>(ctx->ws + Y.snap) : nullptr;
     const bool f32 = sizeof(T) == sizeof(float);
     P.b64 = f32 ? ctx->f<double>(Y.b64) : nullptr;
@@ -573,11 +592,19 @@ void enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
     });
     timed(ctx, KC_MOM_SOURCE, 8, -1,
           [&] { O::mom_source(L, ctx->TL, s, ph, st, S.rn, S.un, S.divu, S.src); });
+    if (p.two_way) {
+        // words: rho^n, u^n x3, rho_j x K, phi x3, F_d x3, a_P and s x3 read;
+        // F_m x3, a_P, s x3 written
+        timed(ctx, KC_MIXTURE, 18.0 + p.n_classes, -1, [&] {
+            O::mixture(L, s, ph, st, p.n_classes, S.rn, S.un, S.rj, S.phin, S.fdn, S.fm, S.aP,
+                       S.src);
+        });
+    }
     T* uin = S.un;
     for (int i = 0; i < p.n_mom_sweeps; ++i) {
         T* uout = (i & 1) ? S.ub : S.ua;
         timed(ctx, KC_MOM_SWEEP, 14, -1,
-              [&] { O::mom_sweep(L, ctx->TL, s, ph, st, uin, uout, S.phin, S.aP, S.src, S.pn); });
+              [&] { O::mom_sweep(L, ctx->TL, s, ph, st, uin, uout, S.mflux, S.aP, S.src, S.pn); });
         uin = uout;
     }
     if (S.snap)   // the predictor's output u*
@@ -598,7 +625,7 @@ void enqueue_corr_setup(pisoc_ctx* ctx, StepPtrs<T>& S, int corr, bool guess) {
     const bool f32 = sizeof(T) == sizeof(float);
     T* ucur = ucur_of(ctx, S);
     timed(ctx, KC_HBYA, 16, -1,
-          [&] { O::hbya(L, ctx->TL, s, ph, ctx->st, ucur, S.hb, S.phin, S.aP, S.src, S.rk, S.w, S.p0); });
+          [&] { O::hbya(L, ctx->TL, s, ph, ctx->st, ucur, S.hb, S.mflux, S.aP, S.src, S.rk, S.w, S.p0); });
     const bool cap = S.snap && corr == 0;
     if (cap) O::cast_out(s, S.w, S.snap + 4 * N, N, 0.0);   // the operator's w = rho/a_P
     timed(ctx, KC_CORR_RHS, f32 ? 14 : 12, -1, [&] {
@@ -686,17 +713,20 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
                 });
                 std::swap(yin, yout);
             }
+            // two-way coupling: the class's face fluxes add up to the next step's F_d
+            const double fdw = S.fdk ? (c == 0 ? 3.0 : 6.0) : 0.0;
             if (ctx->TL.nblocks) {
                 // face fluxes and finish in one tiled pass (words: Y, G, rho_j read, rho_j' written)
-                timed(ctx, KC_DUST_FINISH, 6, -1, [&] {
+                timed(ctx, KC_DUST_FINISH, 6 + fdw, -1, [&] {
                     nb_dust = O::dust_finish_fused(ctx->TL, s, ph, st, yin, S.G, S.rj + c * N,
-                                                   S.rj1 + c * N, ctx->part(PS_DUST + 2 * c));
+                                                   S.rj1 + c * N, ctx->part(PS_DUST + 2 * c),
+                                                   S.fdk, c == 0);
                 });
             } else {
                 timed(ctx, KC_DUST_FACEFLUX, 7, -1, [&] { O::dust_faceflux(L, s, ph, yin, S.G); });
-                timed(ctx, KC_DUST_FINISH, 5, -1, [&] {
+                timed(ctx, KC_DUST_FINISH, 5 + fdw, -1, [&] {
                     O::dust_finish(L, s, ph, st, S.rj + c * N, S.G, S.rj1 + c * N,
-                                   ctx->part(PS_DUST + 2 * c));
+                                   ctx->part(PS_DUST + 2 * c), S.fdk, c == 0);
                 });
             }
         }
@@ -937,6 +967,9 @@ void rotate(pisoc_ctx* ctx) {
     std::swap(ctx->phin, ctx->phik);
     std::swap(ctx->u_idx[0], ctx->u_idx[ctx->ucur_slot]);
     if (ctx->prm.n_classes > 0) std::swap(ctx->rhop, ctx->rhop1);
+    // two-way with dust: this step's F_d becomes the next step's (without dust
+    // both stay zero)
+    if (ctx->prm.two_way && ctx->prm.n_classes > 0) std::swap(ctx->fdn, ctx->fdk);
 }
 
 // Step record of member m from its device state.
@@ -1067,6 +1100,8 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     ctx->phik = lay.phik;
     ctx->rhop = lay.rhop;
     ctx->rhop1 = lay.rhop1;
+    ctx->fdn = lay.fd0;
+    ctx->fdk = lay.fd1;
     ctx->t = 0.0;
     ctx->steps = 0;
     for (int c = 0; c < PISOC_MAX_CORR; ++c) {
@@ -1118,6 +1153,29 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     if (ss != PISOC_OK) return ss;
     ctx->rho_ref.assign(batch, 1.0);
     ctx->p_ref.assign(batch, 1.0);
+    // two-way coupling: the mean mixture density (conserved: gas and dust
+    // masses are), from the initial fields
+    std::vector<double> rhom(batch, 0.0);
+    if (prm->two_way) {
+        for (int m = 0; m < batch; ++m) rhom[m] = ctx->hst[m].red[1] / (double)N;
+        for (int c = 0; c < prm->n_classes; ++c) {
+            for (int m = 0; m < batch; ++m) {
+                Ops<double>::sum_affine_sq(L1, s, ph1, nullptr, d_rho_p[m] + c * N, 0.0, 0.0,
+                                           ctx->part(PS_STAT));
+                finalize_sums(s, ctx->part(PS_STAT), L1.nblocks, 1, 2, ctx->st + m, 0);
+            }
+            pisoc_status sd = sync_state(ctx);
+            if (sd != PISOC_OK) return sd;
+            for (int m = 0; m < batch; ++m) rhom[m] += ctx->hst[m].red[1] / (double)N;
+        }
+        // the gas sums above were overwritten: take them again
+        for (int m = 0; m < batch; ++m) {
+            Ops<double>::sum_affine_sq(L1, s, ph1, nullptr, d_rho[m], 0.0, 0.0, ctx->part(PS_STAT));
+            finalize_sums(s, ctx->part(PS_STAT), L1.nblocks, 1, 2, ctx->st + m, 0);
+        }
+        pisoc_status sg = sync_state(ctx);
+        if (sg != PISOC_OK) return sg;
+    }
     for (int m = 0; m < batch; ++m) {
         const double rr = ctx->hst[m].red[1] / (double)N;
         if (!(rr > 0.0) || !std::isfinite(rr)) {
@@ -1137,6 +1195,7 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
         init.rho_ref = ctx->rho_ref[m];
         init.p_ref = ctx->p_ref[m];
         for (int c = 0; c < prm->n_classes; ++c) init.tau[c] = mprm[m].tau_p[c];
+        init.rhom_mean = rhom[m];
         ctx->hst[m] = init;
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->st, ctx->hst, sizeof(DevState) * (size_t)batch,
@@ -1154,6 +1213,16 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
         }
         Ops<T>::init_phi(ctx->L, s, ctx->ph, ctx->st, ctx->f<T>(ctx->rn), ctx->f<T>(lay.u3[0]),
                          ctx->f<T>(ctx->phin));
+        if (prm->two_way) {
+            // F_d of the initial state; the other buffer starts at zero (it
+            // stays so without dust)
+            (void)hipMemsetAsync(ctx->f<T>(ctx->fdk), 0, 3 * sizeof(T) * NT, s);
+            if (prm->n_classes > 0)
+                Ops<T>::init_fd(ctx->L, s, ctx->ph, prm->n_classes, ctx->f<T>(ctx->rhop),
+                                ctx->f<T>(lay.u3[0]), ctx->f<T>(ctx->fdn));
+            else
+                (void)hipMemsetAsync(ctx->f<T>(ctx->fdn), 0, 3 * sizeof(T) * NT, s);
+        }
     };
     if (prm->precision == PISOC_FP64) convert(double{});
     else convert(float{});
@@ -1709,7 +1778,9 @@ bool same_class_params(const pisoc_params& a, const pisoc_params& b) {
            a.precision == b.precision && a.guess == b.guess &&
            a.d_guess_weights == b.d_guess_weights && a.inner_tol == b.inner_tol &&
            a.max_refine == b.max_refine && a.capture == b.capture &&
-           a.guess_audit == b.guess_audit;
+           a.guess_audit == b.guess_audit && a.two_way == b.two_way &&
+           a.gravity[0] == b.gravity[0] && a.gravity[1] == b.gravity[1] &&
+           a.gravity[2] == b.gravity[2];
 }
 
 // Size classes in order of first appearance; returns false on invalid input.

@@ -62,6 +62,7 @@ class Params(C.Structure):
         ("d_guess_weights", C.c_void_p),
         ("inner_tol", C.c_double), ("max_refine", C.c_int32),
         ("capture", C.c_int32), ("guess_audit", C.c_int32),
+        ("two_way", C.c_int32), ("gravity", C.c_double * 3),
     ]
 
 
@@ -215,7 +216,8 @@ def _stream_ptr(torch, stream):
 def make_params(n, *, gamma, C_, mu, tau_p=(), cfl=0.5, dt_growth=1.2, dt_fixed=0.0, dt_max=0.0,
                 n_corr=2, n_mom_sweeps=4, n_dust_sweeps=4, p_tol=1e-8, p_maxit=500,
                 precision=FP64, guess=GUESS_ZERO, guess_weights=None, inner_tol=1e-7,
-                max_refine=20, capture=False, guess_audit=0) -> Params:
+                max_refine=20, capture=False, guess_audit=0, two_way=False,
+                gravity=(0.0, 0.0, 0.0)) -> Params:
     p = Params()
     p.n = n
     p.n_classes = len(tau_p)
@@ -230,6 +232,9 @@ def make_params(n, *, gamma, C_, mu, tau_p=(), cfl=0.5, dt_growth=1.2, dt_fixed=
     p.inner_tol, p.max_refine = inner_tol, max_refine
     p.capture = 1 if capture else 0
     p.guess_audit = guess_audit
+    p.two_way = 1 if two_way else 0
+    for d in range(3):
+        p.gravity[d] = gravity[d]
     return p
 
 
