@@ -66,7 +66,10 @@ enum {
 /* initial value of each pressure solve */
 enum {
     PISOC_GUESS_ZERO = 0,   /* p' = 0 */
-    PISOC_GUESS_LEARNED = 1 /* 3D conv net prediction; 0 where it does not lower ||r|| */
+    PISOC_GUESS_LEARNED = 1, /* 3D conv net prediction; 0 where it does not lower ||r|| */
+    PISOC_GUESS_PREVIOUS = 2 /* a non-learned rival: the same corrector's solution of the
+                                previous step (the first step starts from 0); the same
+                                rescaling by alpha = g.b / g.(M g) and the same fallback */
 };
 
 /* step-info flag bits */

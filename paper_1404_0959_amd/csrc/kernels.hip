@@ -1620,11 +1620,13 @@ __global__ void __launch_bounds__(kBlock) k_net_input(Phys ph, DevState* st, con
     END_CELLS
 }
 
-// The network's guess g = s1 y and M g (difference form, FP64 arithmetic),
-// stored in the CG scratch vectors, with partial sums g.b and g.(M g).
+// The guess g and M g (difference form, FP64 arithmetic), stored in the CG
+// scratch vectors, with partial sums g.b and g.(M g): g = s1 y for the
+// network's output y, or g = gd (the previous step's solution) when gd is set.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_guess_start(Phys ph, const DevState* st,
                                                         const float* __restrict__ y,
+                                                        const T* __restrict__ gd,
                                                         const T* __restrict__ w,
                                                         const T* __restrict__ diag,
                                                         const T* __restrict__ b,
@@ -1637,12 +1639,14 @@ __global__ void __launch_bounds__(kBlock) k_guess_start(Phys ph, const DevState*
     FOR_CELLS(ph)
     T wv[13];
     float yv[7];
+    T gv[7];
     gather13(w, c, wv);
-    gather7(y, c, yv);
+    if (gd) gather7(gd, c, gv);
+    else gather7(y, c, yv);
     const T dgP = diag[P];
     const double bP = b64 ? b64[P] : (double)b[P];
     loads_issued();
-    auto g = [&](int t) { return s1 * (double)yv[t]; };
+    auto g = [&](int t) { return gd ? (double)gv[t] : s1 * (double)yv[t]; };
     const double gP = g(0);
     double lap = 0.0, sumK = 0.0;
 #pragma unroll
@@ -3371,9 +3375,9 @@ void Ops<T>::net_input(const Launch& L, hipStream_t s, const Phys& ph, DevState*
 }
 template <typename T>
 void Ops<T>::guess_start(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                         const float* y, const T* w, const T* diag, const T* b, const double* b64,
-                         T* g, T* mg, double* part) {
-    LAUNCH(k_guess_start<T>, L, s, ph, st, y, w, diag, b, b64, g, mg, part);
+                         const float* y, const T* gd, const T* w, const T* diag, const T* b,
+                         const double* b64, T* g, T* mg, double* part) {
+    LAUNCH(k_guess_start<T>, L, s, ph, st, y, gd, w, diag, b, b64, g, mg, part);
 }
 template <typename T>
 void Ops<T>::guess_apply(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,

@@ -204,8 +204,9 @@ struct Ops {
     static void net_input(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                           const double* part, const T* b, const T* diag, const T* p0,
                           uint16_t* x4, float* x2, const T* psol, float* tgt);
+    // g = s1 y (y: the network's output) or, with gd set, g = gd
     static void guess_start(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                            const float* y, const T* w, const T* diag, const T* b,
+                            const float* y, const T* gd, const T* w, const T* diag, const T* b,
                             const double* b64, T* g, T* mg, double* part);
     static void guess_apply(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                             const double* part_g, const T* g, const T* mg, const T* diag, T* r,

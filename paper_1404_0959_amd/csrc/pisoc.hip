@@ -72,6 +72,7 @@ struct Layout {
     size_t snap;
     size_t b64, x64a, x64b, xf;  // FP64 refinement fields, FP32 solution copy (FP32 storage only)
     size_t wpk, nx4, na, nb, ny, bsave;  // learned guess: packed weights, activations
+    size_t xprev;  // previous-step guess: each corrector's last solution
     size_t total;
     unsigned max_blocks;     // column length of the partials (all members)
 };
@@ -80,13 +81,13 @@ struct Layout {
 enum KCls {
     KC_CFL, KC_PREDICT, KC_MOM_SOURCE, KC_MOM_SWEEP, KC_HBYA, KC_CORR_RHS, KC_PCG_SPMV,
     KC_CORR_FLUX, KC_CORR_UPDATE, KC_DUDT, KC_DUST_FLUX, KC_DUST_SWEEP,
-    KC_DUST_FACEFLUX, KC_DUST_FINISH, KC_REFINE, KC_NET, KC_MIXTURE, KC_COUNT
+    KC_DUST_FACEFLUX, KC_DUST_FINISH, KC_REFINE, KC_NET, KC_MIXTURE, KC_PREV_GUESS, KC_COUNT
 };
 const char* const kKernelName[KC_COUNT] = {
     "k_cfl", "k_predict", "k_mom_source", "k_mom_sweep", "k_hbya", "k_corr_rhs",
     "k_pcg_spmv", "k_corr_flux", "k_corr_update", "k_dudt", "k_dust_flux",
     "k_dust_sweep", "k_dust_faceflux", "k_dust_finish", "k_refine", "learned_guess",
-    "k_mixture"};
+    "k_mixture", "previous_guess"};
 
 struct Prof {
     bool on = false;
@@ -173,7 +174,9 @@ bool valid_params(const pisoc_params* p, std::string* why) {
     if (p->precision == PISOC_FP32_REFINED &&
         (!(p->inner_tol > 0.0) || !(p->inner_tol < 1.0) || p->max_refine < 1))
         return fail("FP32_REFINED needs 0 < inner_tol < 1 and max_refine >= 1");
-    if (p->guess != PISOC_GUESS_ZERO && p->guess != PISOC_GUESS_LEARNED) return fail("unknown guess");
+    if (p->guess != PISOC_GUESS_ZERO && p->guess != PISOC_GUESS_LEARNED &&
+        p->guess != PISOC_GUESS_PREVIOUS)
+        return fail("unknown guess");
     if (p->guess == PISOC_GUESS_LEARNED && (!p->d_guess_weights || p->n % 16 != 0))
         return fail("learned guess needs d_guess_weights and n % 16 == 0");
     if (p->guess_audit < 0) return fail("guess_audit must be >= 0");
@@ -212,8 +215,13 @@ Layout make_layout(const pisoc_params* p, int batch) {
         L.fd1 = take(3 * es * N);
         L.fm = take(3 * es * N);
     }
-    L.snap = p->capture ? take((p->guess == PISOC_GUESS_LEARNED ? 10 : 8) * sizeof(double) * N)
+    L.snap = p->capture ? take((p->guess != PISOC_GUESS_ZERO ? 10 : 8) * sizeof(double) * N)
                         : 0;
+    if (p->guess == PISOC_GUESS_PREVIOUS) {
+        // each corrector's solution of the last step, and the saved b of a fallback
+        L.xprev = take(es * N * (size_t)p->n_corr);
+        L.bsave = take(es * N);
+    }
     if (p->guess == PISOC_GUESS_LEARNED) {
         L.wpk = take(net_packed_bytes());
         L.nx4 = take(4 * 2 * N);
@@ -462,12 +470,15 @@ pisoc_status run_pcg(pisoc_ctx* ctx, const CgVecs<T>& v, bool fresh, int iters, 
     return PISOC_OK;
 }
 
-// The learned initial guess of one pressure solve, every member: scaled inputs
-// from the system just set up, the network on the matrix cores, CG started from
-// x0 = alpha s1 y (alpha energy-optimal); a member whose guess does not lower
-// ||b - M x0|| below ||b|| falls back to x0 = 0 (decided on the device).
+// The initial guess of one pressure solve, every member: the learned one
+// (scaled inputs from the system just set up, the network on the matrix cores,
+// g = s1 y) or the previous step's solution of the same corrector (g = gprev);
+// CG then starts from x0 = alpha g (alpha energy-optimal); a member whose guess
+// does not lower ||b - M x0|| below ||b|| falls back to x0 = 0 (decided on the
+// device).
 template <typename T>
-void learned_guess(pisoc_ctx* ctx, T* r, T* x, T* dg, T* w, T* p0, T* gbuf, T* mgbuf) {
+void guess_solve_start(pisoc_ctx* ctx, const T* gprev, T* r, T* x, T* dg, T* w, T* p0, T* gbuf,
+                       T* mgbuf) {
     using O = Ops<T>;
     const Layout& Y = ctx->lay;
     const bool f32 = sizeof(T) == sizeof(float);
@@ -475,14 +486,17 @@ void learned_guess(pisoc_ctx* ctx, T* r, T* x, T* dg, T* w, T* p0, T* gbuf, T* m
     double* x64 = f32 ? ctx->f<double>(Y.x64a) : nullptr;
     double* b64 = f32 ? ctx->f<double>(Y.b64) : nullptr;
     T* bsave = ctx->f<T>(Y.bsave);
-    timed(ctx, KC_NET, 2, -1, [&] {
-        O::net_stats(ctx->L, s, ctx->ph, r, dg, p0, ctx->part(PS_STAT));
-        O::net_input(ctx->L, s, ctx->ph, ctx->st, ctx->part(PS_STAT), r, dg, p0,
-                     ctx->f<uint16_t>(Y.nx4), nullptr, nullptr, nullptr);
-        net_forward(s, ctx->prm.n, ctx->batch, ctx->ws + Y.wpk, ctx->f<uint16_t>(Y.nx4),
-                    ctx->f<uint16_t>(Y.na), ctx->f<uint16_t>(Y.nb), ctx->f<float>(Y.ny), 1.f);
-        O::guess_start(ctx->L, s, ctx->ph, ctx->st, ctx->f<float>(Y.ny), w, dg, r, b64, gbuf,
-                       mgbuf, ctx->part(PS_STAT));
+    const bool learned = ctx->prm.guess == PISOC_GUESS_LEARNED;
+    timed(ctx, learned ? KC_NET : KC_PREV_GUESS, 2, -1, [&] {
+        if (learned) {
+            O::net_stats(ctx->L, s, ctx->ph, r, dg, p0, ctx->part(PS_STAT));
+            O::net_input(ctx->L, s, ctx->ph, ctx->st, ctx->part(PS_STAT), r, dg, p0,
+                         ctx->f<uint16_t>(Y.nx4), nullptr, nullptr, nullptr);
+            net_forward(s, ctx->prm.n, ctx->batch, ctx->ws + Y.wpk, ctx->f<uint16_t>(Y.nx4),
+                        ctx->f<uint16_t>(Y.na), ctx->f<uint16_t>(Y.nb), ctx->f<float>(Y.ny), 1.f);
+        }
+        O::guess_start(ctx->L, s, ctx->ph, ctx->st, learned ? ctx->f<float>(Y.ny) : nullptr,
+                       learned ? nullptr : gprev, w, dg, r, b64, gbuf, mgbuf, ctx->part(PS_STAT));
         O::guess_apply(ctx->L, s, ctx->ph, ctx->st, ctx->part(PS_STAT), gbuf, mgbuf, dg, r, x,
                        x64, b64, bsave, ctx->part(PS_U));
         // totals of r0.z0, ||r0||^2, ||b||^2 into red[0..2], then the fallback test
@@ -635,7 +649,10 @@ void enqueue_corr_setup(pisoc_ctx* ctx, StepPtrs<T>& S, int corr, bool guess) {
                                     S.b64);
     });
     if (guess) {
-        learned_guess<T>(ctx, S.r, S.x, S.dg, S.w, S.p0, S.pp0, S.q);
+        const T* gprev = ctx->prm.guess == PISOC_GUESS_PREVIOUS
+                             ? ctx->f<T>(ctx->lay.xprev) + (size_t)corr * N
+                             : nullptr;
+        guess_solve_start<T>(ctx, gprev, S.r, S.x, S.dg, S.w, S.p0, S.pp0, S.q);
         ctx->nb_start = L.nblocks;   // the guess rewrites the start's partials
         if (cap) {
             // the network's guess g (left in pp0) and the solve's start x0 (x, or
@@ -849,7 +866,14 @@ void solve_fp32(pisoc_ctx* ctx, StepPtrs<float>& S, int corr, bool guess, bool e
 }
 
 bool audit_on(const pisoc_ctx* ctx) {
-    return ctx->prm.guess == PISOC_GUESS_LEARNED && ctx->prm.guess_audit > 0 && ctx->audit.have_events;
+    return ctx->prm.guess != PISOC_GUESS_ZERO && ctx->prm.guess_audit > 0 && ctx->audit.have_events;
+}
+
+// A guess exists for this step: the learned one always, the previous-step one
+// once a step has been taken.
+bool guess_available(const pisoc_ctx* ctx) {
+    return ctx->prm.guess == PISOC_GUESS_LEARNED ||
+           (ctx->prm.guess == PISOC_GUESS_PREVIOUS && ctx->steps > 0);
 }
 
 // The guess is used for a solve when the iterations it saves exceed its cost
@@ -924,8 +948,9 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
     // captured one the verdict it was built with (audit_decide_capture)
     const bool audit = eager && audit_on(ctx);
     for (int corr = 0; corr < p.n_corr; ++corr) {
-        const bool guess =
-            p.guess == PISOC_GUESS_LEARNED && (!audit_on(ctx) || ctx->audit.use[corr]);
+        // a step without a guess available counts as one without the guess
+        if (audit && !guess_available(ctx)) ctx->audit.use[corr] = false;
+        const bool guess = guess_available(ctx) && (!audit_on(ctx) || ctx->audit.use[corr]);
         if (audit && guess) (void)hipEventRecord(ctx->audit.ev[corr][0], s);
         enqueue_corr_setup<T>(ctx, S, corr, guess);
         if (audit && guess) (void)hipEventRecord(ctx->audit.ev[corr][1], s);
@@ -946,6 +971,15 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
         }
         if (err != PISOC_OK) return err;
         if (audit && guess) (void)hipEventRecord(ctx->audit.ev[corr][2], s);
+        if (p.guess == PISOC_GUESS_PREVIOUS) {
+            // the solution the corrector applies: the next step's guess
+            T* xp = ctx->f<T>(ctx->lay.xprev) + (size_t)corr * ctx->NT();
+            if (hipMemcpyAsync(xp, S.x, sizeof(T) * ctx->NT(), hipMemcpyDeviceToDevice, s) !=
+                hipSuccess) {
+                ctx->err = "hipMemcpyAsync failed";
+                return PISOC_ERR_HIP;
+            }
+        }
         if (eager) {
             for (int m = 0; m < ctx->batch; ++m)
                 if (ctx->hst[m].flags & PISOC_FLAG_BAD_DT) {
@@ -1119,7 +1153,7 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     ctx->audit.cost = -1.0;
     ctx->audit.steps = 0;
     ctx->audit.have_events = false;
-    if (prm->guess == PISOC_GUESS_LEARNED && prm->guess_audit > 0) {
+    if (prm->guess != PISOC_GUESS_ZERO && prm->guess_audit > 0) {
         bool ok = true;
         for (auto& row : ctx->audit.ev)
             for (auto& e : row)   // timing only, as the profiler's
@@ -1292,8 +1326,8 @@ pisoc_status member_fields(pisoc_ctx* ctx, int m, uint32_t which, double* const*
                     return PISOC_ERR_INVALID;
                 }
                 const bool gsel = mk == PISOC_FIELD_GUESS || mk == PISOC_FIELD_GUESS_X0;
-                if (gsel && ctx->prm.guess != PISOC_GUESS_LEARNED) {
-                    ctx->err = "captured guess requested without the learned guess";
+                if (gsel && ctx->prm.guess == PISOC_GUESS_ZERO) {
+                    ctx->err = "captured guess requested without a guess";
                     return PISOC_ERR_INVALID;
                 }
                 const int idx = mk == PISOC_FIELD_PSOLVE_B ? 0
@@ -2250,7 +2284,7 @@ pisoc_status pisoc_ens_class_info(const pisoc_ens* e, int32_t cls, pisoc_ens_cla
     o.cap_later = e->built ? ctx->cap_later_built : ctx->cap_later;
     for (int c = 0; c < PISOC_MAX_CORR; ++c) o.caps[c] = e->built ? ctx->caps_built[c] : ctx->caps[c];
     for (int c = 0; c < ctx->prm.n_corr; ++c)
-        if (ctx->prm.guess == PISOC_GUESS_LEARNED && (!audit_on(ctx) || ctx->audit.use[c]))
+        if (ctx->prm.guess != PISOC_GUESS_ZERO && (!audit_on(ctx) || ctx->audit.use[c]))
             o.guess_mask |= 1 << c;
     o.cg_cells_z = ctx->TS.nblocks ? ctx->TS.cz : 0;
     o.tiled_cells_z = ctx->TL.nblocks ? ctx->TL.cz : 0;

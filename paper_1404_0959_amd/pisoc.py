@@ -19,7 +19,7 @@ MAX_CORR = 4
 OK, WARN_NOT_CONVERGED, WARN_GUESS_FALLBACK, WARN_DUST = 0, 1, 2, 3
 ERR_INVALID, ERR_HIP, ERR_DIVERGED, ERR_WORKSPACE = -1, -2, -3, -4
 FP64, FP32_REFINED = 0, 1
-GUESS_ZERO, GUESS_LEARNED = 0, 1
+GUESS_ZERO, GUESS_LEARNED, GUESS_PREVIOUS = 0, 1, 2
 FLAG_PCG_MAXIT, FLAG_NONFINITE, FLAG_RHO_NONPOS, FLAG_GUESS_FALLBACK, FLAG_BAD_DT = 1, 2, 4, 8, 16
 FLAG_GUESS_SKIPPED = 32
 FLAG_DUST_NEG, FLAG_DUST_NONFINITE, FLAG_DUST_DIAG = 64, 128, 256

@@ -156,3 +156,52 @@ def test_learned_guess_gain_unseen_seeds(P, weights):
             g = iterations(P, case, steps, weights, **kw)
             print(f"{n}^3 seed 20 {prec}, {steps} steps: zero {z}, learned {g} "
                   f"({g / z - 1:+.1%})")
+
+
+# ------------------------------------------------------------ previous-step guess
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_previous_guess_start_vs_oracle(P, ora, precision):
+    """The non-learned rival: the second step's corrector-1 solve starts from
+    the first step's corrector-1 solution g (captured bitwise as the guess),
+    rescaled and checked by the oracle's rule on the oracle's operator."""
+    case = make_hit_case(32, 23, mach=0.2, stokes=(0.1,))
+    kw = dict(p_tol=1e-8) if precision == "fp64" else dict(
+        p_tol=1e-6, precision=P.FP32_REFINED, inner_tol=1e-6)
+    o = ora.Oracle.from_case(case, p_tol=kw["p_tol"], capture=True)
+    s = P.Solver.from_case(case, capture=True, guess=P.GUESS_PREVIOUS, **kw)
+    o.step(1)
+    st, info = s.step(1)
+    assert not info[0]["flags"] & P.FLAG_GUESS_FALLBACK
+    x1 = s.get(P.FIELD_PSOLVE_X).cpu().numpy()
+    o.step(1)
+    st, info = s.step(1)
+    f = s.fields(P.FIELD_PSOLVE_B | P.FIELD_GUESS | P.FIELD_GUESS_X0)
+    b, g, x0 = (f[k].cpu().numpy() for k in (P.FIELD_PSOLVE_B, P.FIELD_GUESS, P.FIELD_GUESS_X0))
+    if precision == "fp64":
+        assert np.array_equal(g, x1)
+    else:   # the FP32 copy of the solution the corrector applied
+        assert np.max(np.abs(g - x1)) <= 1e-6 * np.max(np.abs(x1))
+    x0o, alpha, ratio, fell = ora.guess_start(o.get(ora.SYS_PSIDT, 0), o.get(ora.SYS_K, 0), b, g)
+    print(f"previous guess {precision}: alpha {alpha:.6f}, start residual ratio {ratio:.4f}")
+    # (the step's fallback flag covers both correctors; corrector 1's start is x0)
+    assert fell == (np.max(np.abs(x0)) == 0.0)
+    tol = 1e-9 if precision == "fp64" else 1e-5
+    assert np.max(np.abs(x0 - x0o)) <= tol * np.max(np.abs(x0o))
+    for i in info:
+        assert max(i["pcg_relres"]) <= kw["p_tol"]
+
+
+def test_previous_guess_iterations(P):
+    """Iterations saved by the previous-step guess at residual 1e-6 (printed
+    for 32^3, 128^3 and 256^3 in both precisions; every solve meets the
+    tolerance)."""
+    for n, steps in ((32, 10), (128, 5), (256, 4)):
+        case = make_hit_case(n, 20, mach=0.2, stokes=(0.2,))
+        for prec, kw in (("fp64", {}), ("fp32", dict(precision=P.FP32_REFINED, inner_tol=1e-6))):
+            z = iterations(P, case, steps, **kw)
+            s = P.Solver.from_case(case, p_tol=1e-6, guess=P.GUESS_PREVIOUS, **kw)
+            st, info = s.step(steps)
+            assert st >= 0 and all(max(i["pcg_relres"]) <= 1e-6 for i in info)
+            g = sum(sum(i["pcg_iters"]) for i in info)
+            print(f"previous guess {n}^3 {prec}, {steps} steps: zero {z}, previous {g} "
+                  f"({g / z - 1:+.1%})")
