@@ -329,7 +329,8 @@ def main():
                                f"CFL 0.5, 2 PISO correctors, Jacobi-PCG rel. residual "
                                f"{args.p_tol:g}, seed {args.seed}",
                    "grid": args.n, "mode": head,
-                   "guess": (f"learned, audited every {args.guess_audit} steps"
+                   "guess": (f"learned, audited (trial of the rejected choice after {args.guess_audit} "
+                             f"steps, the interval doubling up to {16 * args.guess_audit})"
                              if head == "fp32_learned" else "zero")},
         "roofline": roof,
         "cpu_baseline": cpu,

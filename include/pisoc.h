@@ -119,7 +119,9 @@ typedef struct {
                                   iterations it saves (running means of solves with and
                                   without it) exceed its own cost in CG-iteration
                                   equivalents (timed with events), trying the other choice
-                                  once every k steps (PISOC_FLAG_GUESS_SKIPPED marks steps
+                                  once after k steps and then at intervals that double, up
+                                  to 16 k, while each trial confirms the verdict (back to k
+                                  when one overturns it; PISOC_FLAG_GUESS_SKIPPED marks steps
                                   that went without it).  Eager ensemble steps audit the
                                   same way; a captured ensemble step keeps the verdict
                                   its graph was built with (without the periodic trial) */

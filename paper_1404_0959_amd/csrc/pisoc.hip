@@ -290,6 +290,12 @@ struct pisoc_ctx {
         double cost;
         bool use[PISOC_MAX_CORR];   // this step's choice
         int64_t steps;
+        // probes of the choice the verdict rejects: the next one at step
+        // next_probe; the interval doubles (up to kMaxProbeFactor guess_audit)
+        // while probes confirm the verdict, and starts again at guess_audit
+        // when one overturns it
+        int64_t next_probe, period;
+        bool probing, verdict[PISOC_MAX_CORR];
         hipEvent_t ev[PISOC_MAX_CORR][3];
         bool have_events;
     } audit;
@@ -880,16 +886,26 @@ bool guess_available(const pisoc_ctx* ctx) {
 // (both as running means); until both options have been measured each is
 // tried once, and every guess_audit-th step takes the other option once so
 // that the mean of the unused one stays current.
+constexpr int kMaxProbeFactor = 16;
+bool audit_measured(const pisoc_ctx* ctx);
+
+bool audit_pays(const pisoc_ctx* ctx, int c) {
+    const auto& A = ctx->audit;
+    return A.it_zero[c] - A.it_guess[c] > std::max(A.cost, 0.0);
+}
+
 void audit_decide(pisoc_ctx* ctx) {
     auto& A = ctx->audit;
-    const bool probe = A.steps % ctx->prm.guess_audit == ctx->prm.guess_audit - 1;
+    const bool measured = audit_measured(ctx);
+    A.probing = measured && A.steps >= A.next_probe;
     for (int c = 0; c < ctx->prm.n_corr; ++c) {
         bool use;
         if (A.it_guess[c] < 0.0) use = true;
         else if (A.it_zero[c] < 0.0) use = false;
         else {
-            const bool pays = A.it_zero[c] - A.it_guess[c] > std::max(A.cost, 0.0);
-            use = probe ? !pays : pays;
+            const bool pays = audit_pays(ctx, c);
+            A.verdict[c] = pays;
+            use = A.probing ? !pays : pays;
         }
         A.use[c] = use;
     }
@@ -928,6 +944,15 @@ void audit_update(pisoc_ctx* ctx) {
         if (hipEventElapsedTime(&t_guess, A.ev[c][0], A.ev[c][1]) == hipSuccess &&
             hipEventElapsedTime(&t_solve, A.ev[c][1], A.ev[c][2]) == hipSuccess && t_solve > 0.f)
             A.cost = mean(A.cost, (double)t_guess / ((double)t_solve / std::max(it, 1)));
+    }
+    if (A.probing) {
+        bool confirmed = true;
+        for (int c = 0; c < ctx->prm.n_corr; ++c)
+            confirmed = confirmed && audit_pays(ctx, c) == A.verdict[c];
+        const int64_t base = ctx->prm.guess_audit;
+        A.period = confirmed ? std::min(2 * A.period, kMaxProbeFactor * base) : base;
+        A.next_probe = A.steps + A.period;
+        A.probing = false;
     }
     A.steps += 1;
 }
@@ -1152,6 +1177,9 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     }
     ctx->audit.cost = -1.0;
     ctx->audit.steps = 0;
+    ctx->audit.period = std::max(prm->guess_audit, 1);
+    ctx->audit.next_probe = ctx->audit.period - 1;
+    ctx->audit.probing = false;
     ctx->audit.have_events = false;
     if (prm->guess != PISOC_GUESS_ZERO && prm->guess_audit > 0) {
         bool ok = true;
