@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--ens-steps", type=int, default=20)
     ap.add_argument("--ens-seq-steps", type=int, default=3,
                     help="timed steps per member of the sequential single-grid runs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the two-way coupling and diagnostics measurements")
     return ap.parse_args()
 
 
@@ -199,6 +201,60 @@ def ensemble_run(P, torch, args, weights):
     return out
 
 
+def extras_run(P, torch, case, args):
+    """The other rows of the step at the benchmark's size: the two-way coupled
+    mixture with gravity settling (FP32 refined, same workload, dust loading
+    raised to 0.2), and the flow diagnostics on the velocity field, each with
+    its algorithmic bytes (words each kernel must read or write once)."""
+    import numpy as np
+    out = {}
+    n3 = args.n ** 3
+    kw = dict(p_tol=args.p_tol, cfl=0.5, n_corr=2, n_mom_sweeps=4, n_dust_sweeps=4,
+              precision=P.FP32_REFINED, inner_tol=args.inner_tol, two_way=True,
+              gravity=(0.0, 0.0, -1.0))
+    s = P.Solver(case.n, case.rho, case.u, case.rho_p * 200.0, gamma=case.gamma, C_=case.C,
+                 mu=case.mu, tau_p=case.tau_p, **kw)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info = s.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["two_way_fp32"] = dict(value=n3 * args.steps / el, unit="cell-steps/s",
+                               ms_per_step=el * 1e3 / args.steps, status=st,
+                               pcg_iters_mean=float(np.mean([np.mean(i["pcg_iters"]) for i in info])))
+    log(f"two-way FP32: {el * 1e3 / args.steps:.3f} ms/step")
+    u = s.get(P.FIELD_U)
+    s.close()
+    del s
+
+    def time_it(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+    diag = {}
+    # bytes per cell: spectrum, per component: the real field read (8), three
+    # FFT passes reading and writing the complex field (3 x 32), the shell
+    # binning reading it (16); Q: 3 velocity words read, Q written; filtered
+    # statistics: u read (24) and nine filtered fields written (72), then read
+    # back (72)
+    for name, fn, bpc in (("spectrum", lambda: P.spectrum(u), 3 * (8 + 96 + 16)),
+                          ("qcriterion", lambda: P.qcriterion(u), 32),
+                          ("filtered_stats", lambda: P.sgs_stats(u), 168)):
+        t = time_it(fn)
+        diag[name] = dict(ms=round(t * 1e3, 3), gbs=round(bpc * n3 / t / 1e9, 1),
+                          bytes_per_cell=bpc)
+        log(f"{name}: {t * 1e3:.3f} ms, {bpc * n3 / t / 1e9:.1f} GB/s")
+    E, lam, D = P.spectrum(u)
+    diag["taylor_microscale"] = lam
+    out["diagnostics"] = diag
+    return out
+
+
 KERNEL_SOURCES = ("kernels.hip", "device.hpp", "launch.hpp", "net.hip")
 # dominant kernel class -> the 256^3 kernels whose HBM bytes the committed
 # counter summary holds (template instances of one kernel class are averaged
@@ -305,6 +361,9 @@ def main():
     ens = None
     if not args.no_ensemble:
         ens = ensemble_run(P, torch, args, weights)
+    extras = None
+    if not args.no_extras:
+        extras = extras_run(P, torch, case, args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -341,6 +400,7 @@ def main():
                       if m == "fp32_learned" else 0} for m, r in runs.items()},
         "kernels": kernels,
         "ensemble": ens,
+        "extras": extras,
     }
     if "fp64" in runs and head != "fp64":
         out["speedup_vs_fp64"] = runs[head]["value"] / runs["fp64"]["value"]

@@ -13,7 +13,7 @@
 // s + 1/2, E(s) = sum over the shell of |u_hat|^2 / 2, so sum_s E(s) =
 // <|u|^2>/2.  Taylor micro-scale lambda = sqrt(5 sum E / D) with D = sum_k
 // |k|^2 |u_hat(k)|^2 / 2.  Every sum runs in a fixed order (bitwise
-// reproducible): per z-plane of wavevectors and shell, then over planes.
+// reproducible): per row of wavevectors, per plane, then over the planes.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -29,9 +29,7 @@ namespace {
 using cplx = double2;
 
 constexpr int kFftThreads = 256;
-constexpr int kFftLds = 2048;        // complex values per LDS buffer (two buffers)
-constexpr int kBinChunk = 2048;      // cells per LDS chunk of the shell binning
-constexpr int kMaxOwned = 4;         // shells per thread: bins <= 4 * 256
+constexpr int kFftLds = 1024;        // complex values per LDS buffer (two buffers)
 
 bool pow2(int n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0; }
 int ilog2(int n) {
@@ -68,7 +66,13 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_axis(cplx* f, const double*
     extern __shared__ cplx lds_fft[];
     cplx* A = lds_fft;
     cplx* B = lds_fft + L * n;
+    cplx* W = lds_fft + 2 * L * n;   // twiddles exp(-2 pi i m / n), m < n/2
     const int tid = threadIdx.x;
+    for (int m = tid; m < n / 2; m += kFftThreads) {
+        double sn, cs;
+        sincospi(-2.0 * (double)m / (double)n, &sn, &cs);
+        W[m] = {cs, sn};
+    }
     const size_t nn = (size_t)n * n;
     const int first = blockIdx.x * L;          // first line of the block
     auto addr = [&](int l, int e) -> size_t {
@@ -92,8 +96,9 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_axis(cplx* f, const double*
         for (int t = tid; t < L * half; t += kFftThreads) {
             const int l = t / half, j = t - l * half;
             const int k = j & (Ns - 1);
-            double sn, cs;
-            sincospi(-(double)k / (double)Ns, &sn, &cs);
+            // exp(-i pi k / Ns) = exp(-2 pi i (k n / (2 Ns)) / n)
+            const cplx tw = W[k * (half / Ns)];
+            const double cs = tw.x, sn = tw.y;
             const cplx a = A[l * n + j], x = A[l * n + j + half];
             const cplx wb = {x.x * cs - x.y * sn, x.x * sn + x.y * cs};
             const int base = l * n + 2 * (j - k) + k;
@@ -115,71 +120,75 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_axis(cplx* f, const double*
 // Signed wavenumber of DFT index i (components in [-n/2, n/2)).
 __device__ inline int wavenumber(int i, int n) { return i < n / 2 ? i : i - n; }
 
-// Shell binning of one component's transform f: block z (one plane of
-// wavevectors) adds e = |f|^2 / (2 n^6) of each of its cells to its shell.
-// The plane's cells pass through LDS in chunks; thread t owns the shells
-// s = t + 256 q and sums, in cell order, the entries of the chunk that fall
-// in them.  part[z * (bins + 1) + s] receives the plane's shell sums, and
-// part[z * (bins + 1) + bins] its sum of |k|^2 e (block reduction).
-__global__ void __launch_bounds__(kFftThreads) k_spectrum_bin(const cplx* f, int n, int bins,
-                                                            double inv_n6, double* part) {
-    __shared__ double ce[kBinChunk];
-    __shared__ int cs[kBinChunk];
-    __shared__ double red[16];
-    const int tid = threadIdx.x;
-    const int kz = wavenumber(blockIdx.x, n);
-    const size_t nn = (size_t)n * n;
-    const cplx* plane = f + nn * blockIdx.x;
-    double own[kMaxOwned] = {0.0, 0.0, 0.0, 0.0};
-    double dk = 0.0;
-    for (size_t c0 = 0; c0 < nn; c0 += kBinChunk) {
-        for (int t = tid; t < kBinChunk; t += kFftThreads) {
-            const size_t c = c0 + t;
-            if (c < nn) {
-                const int i = (int)(c % n), j = (int)(c / n);
-                const int kx = wavenumber(i, n), ky = wavenumber(j, n);
-                const int64_t k2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
-                const cplx v = plane[c];
-                const double e = 0.5 * (v.x * v.x + v.y * v.y) * inv_n6;
-                ce[t] = e;
-                cs[t] = shell_of(k2);
-                dk += (double)k2 * e;
-            } else {
-                ce[t] = 0.0;
-                cs[t] = -1;
-            }
+// Shell binning of one component's transform f, in three fixed-order passes.
+// 1. One thread per x-row of wavevectors (fixed ky, kz): walking kx in order of
+//    |kx| (0, 1, -1, 2, -2, ..., -n/2) the shell index never decreases, so the
+//    row's energies e = |f|^2 / (2 n^6) sum into runs, one per shell, written to
+//    rowpart[row][s - s0] with s0 the shell of kx = 0 (W = n/2 + 2 entries per
+//    row hold every shell the row reaches; shells it skips stay 0); rowd[row]
+//    receives the row's sum of |k|^2 e.
+__global__ void __launch_bounds__(kFftThreads) k_spectrum_rows(const cplx* f, int n, int W,
+                                                             double inv_n6, double* rowpart,
+                                                             double* rowd) {
+    const size_t row = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= (size_t)n * n) return;
+    const int ky = wavenumber((int)(row % n), n), kz = wavenumber((int)(row / n), n);
+    const int64_t kyz = (int64_t)ky * ky + (int64_t)kz * kz;
+    const int s0 = shell_of(kyz);
+    double* out = rowpart + row * (size_t)W;
+    for (int t = 0; t < W; ++t) out[t] = 0.0;
+    const cplx* line = f + row * (size_t)n;
+    int cur = s0;
+    double acc = 0.0, dk = 0.0;
+    for (int m = 0; m < n; ++m) {
+        const int kx = m == 0 ? 0 : m == n - 1 ? -n / 2 : (m & 1) ? (m + 1) / 2 : -(m / 2);
+        const cplx v = line[kx >= 0 ? kx : kx + n];
+        const double e = 0.5 * (v.x * v.x + v.y * v.y) * inv_n6;
+        const int64_t k2 = kyz + (int64_t)kx * kx;
+        const int sh = shell_of(k2);
+        if (sh != cur) {
+            out[cur - s0] = acc;
+            acc = 0.0;
+            cur = sh;
         }
-        __syncthreads();
-        for (int t = 0; t < kBinChunk; ++t) {
-            const int s = cs[t];
-            if (s >= 0 && (s & (kFftThreads - 1)) == tid) {
-                const int q = s / kFftThreads;
-#pragma unroll
-                for (int r = 0; r < kMaxOwned; ++r)   // a select, not a dynamic register index
-                    if (r == q) own[r] += ce[t];
-            }
-        }
-        __syncthreads();
+        acc += e;
+        dk += (double)k2 * e;
     }
-    double* out = part + (size_t)blockIdx.x * (bins + 1);
-    for (int q = 0; q < kMaxOwned; ++q) {
-        const int s = tid + q * kFftThreads;
-        if (s < bins) out[s] = own[q];
-    }
-    double v[1] = {dk};
-    block_reduce<1, 0u>(v, red);
-    if (tid == 0) out[bins] = v[0];
+    out[cur - s0] = acc;
+    rowd[row] = dk;
 }
 
-// Totals over the planes (in plane order) and over the three components'
-// partial sets (in component order): out[s] = E(s), out[bins] = D.
-__global__ void __launch_bounds__(kFftThreads) k_spectrum_total(const double* part, int n,
+// 2. Per plane kz and shell s: the sum over the plane's rows in row order
+//    (s = bins: the rows' |k|^2 e sums) into plane[kz * (bins + 1) + s].
+__global__ void __launch_bounds__(64) k_spectrum_planes(const double* rowpart, const double* rowd,
+                                                        int n, int W, int bins, double* plane) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int zi = blockIdx.y;
+    if (s > bins) return;
+    const int kz = wavenumber(zi, n);
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const size_t row = (size_t)j + (size_t)n * zi;
+        if (s == bins) {
+            acc += rowd[row];
+            continue;
+        }
+        const int ky = wavenumber(j, n);
+        const int t = s - shell_of((int64_t)ky * ky + (int64_t)kz * kz);
+        if (t >= 0 && t < W) acc += rowpart[row * (size_t)W + t];
+    }
+    plane[(size_t)zi * (bins + 1) + s] = acc;
+}
+
+// 3. Totals over the planes (in plane order) and over the three components'
+//    plane sets (in component order): out[s] = E(s), out[bins] = D.
+__global__ void __launch_bounds__(kFftThreads) k_spectrum_total(const double* part, int nblk,
                                                               int bins, double* out) {
-    const size_t set = (size_t)n * (bins + 1);
+    const size_t set = (size_t)nblk * (bins + 1);
     for (int s = threadIdx.x; s <= bins; s += kFftThreads) {
         double acc = 0.0;
         for (int c = 0; c < 3; ++c)
-            for (int z = 0; z < n; ++z) acc += part[c * set + (size_t)z * (bins + 1) + s];
+            for (int b = 0; b < nblk; ++b) acc += part[c * set + (size_t)b * (bins + 1) + s];
         out[s] = acc;
     }
 }
@@ -328,6 +337,7 @@ DiagLayout diag_layout(int n) {
         return o;
     };
     // the spectrum's complex field or the nine filtered fields (never both at once)
+    // (the spectrum's row sums follow its complex field inside the same region)
     d.field = take(sizeof(double) * 9 * N);
     d.part = take(sizeof(double) * 3 * (size_t)n * (bins + 1));
     d.total_out = take(sizeof(double) * (bins + 1));
@@ -368,9 +378,13 @@ pisoc_status pisoc_diag_spectrum(int32_t n, const double* d_u, double* h_E, int3
     const size_t N = (size_t)n * n * n;
     const int L = fft_lines(n), logn = ilog2(n);
     const unsigned blocks = (unsigned)((size_t)n * n / L);
-    const size_t lds = 2 * sizeof(cplx) * (size_t)L * n;
+    const size_t lds = sizeof(cplx) * (2 * (size_t)L * n + n / 2);
     const double inv_n6 = 1.0 / ((double)N * (double)N);
+    const int W = n / 2 + 2;
+    double* rowpart = reinterpret_cast<double*>(ws + Ly.field + sizeof(cplx) * N);
+    double* rowd = rowpart + (size_t)n * n * W;
     const size_t set = (size_t)n * (nbins + 1);
+    const unsigned rowblocks = (unsigned)(((size_t)n * n + kFftThreads - 1) / kFftThreads);
     for (int c = 0; c < 3; ++c) {
         hipLaunchKernelGGL(k_fft_axis<0>, dim3(blocks), dim3(kFftThreads), lds, s, f, d_u + c * N,
                            n, logn, L);
@@ -378,8 +392,10 @@ pisoc_status pisoc_diag_spectrum(int32_t n, const double* d_u, double* h_E, int3
                            logn, L);
         hipLaunchKernelGGL(k_fft_axis<2>, dim3(blocks), dim3(kFftThreads), lds, s, f, nullptr, n,
                            logn, L);
-        hipLaunchKernelGGL(k_spectrum_bin, dim3(n), dim3(kFftThreads), 0, s, f, n, nbins, inv_n6,
-                           part + c * set);
+        hipLaunchKernelGGL(k_spectrum_rows, dim3(rowblocks), dim3(kFftThreads), 0, s, f, n, W,
+                           inv_n6, rowpart, rowd);
+        hipLaunchKernelGGL(k_spectrum_planes, dim3((nbins + 64) / 64, n), dim3(64), 0, s, rowpart,
+                           rowd, n, W, nbins, part + c * set);
     }
     hipLaunchKernelGGL(k_spectrum_total, dim3(1), dim3(kFftThreads), 0, s, part, n, nbins, tot);
     if (hipGetLastError() != hipSuccess) return PISOC_ERR_HIP;
