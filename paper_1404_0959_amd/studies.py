@@ -2,6 +2,7 @@
 
     python -m paper_1404_0959_amd.studies precision [--n 256] [--steps 200]
     python -m paper_1404_0959_amd.studies stats [--n 128] [--steps 500]
+    python -m paper_1404_0959_amd.studies stokes [--n 128] [--steps 500] [--mach 0.5]
 
 precision: the FP32 mode (FP32 fields and inner CG, FP64 residual
 refinement, reductions and mass budget) against plain FP64 on the same seeded
@@ -18,6 +19,11 @@ stats: the plain FP64 method at 128^3, Mach 0.5, three dust classes (Stokes
 0.05, 0.2, 0.5), adaptive dt at CFL 0.5, statistics every 10 steps: energy,
 enstrophy, density and Mach r.m.s., concentration variance per class and the
 gas and dust mass budgets.
+
+stokes: one run per Stokes number at 128^3 (default Mach 0.5): when the dust
+flags first rise (negative bulk density, non-positive implicit diagonal),
+the concentration variance over time and the smallest relative dust density,
+which bound the Stokes range where the transport reading stays usable.
 """
 from __future__ import annotations
 
@@ -105,9 +111,50 @@ def stats_run(n=128, steps=500, every=10, seed=0, p_tol=1e-8, mach=0.5,
                 gas_mass_drift_max=drift, dust_mass_drift_max=pdrift)
 
 
+def stokes_range(n=128, steps=500, every=10, seed=0, p_tol=1e-8, mach=0.5,
+                 stokes=(0.025, 0.05, 0.1, 0.2, 0.3, 0.5), log=print):
+    """One run per Stokes number (one dust class each): the first steps at which
+    the dust flags are raised (a negative bulk density; a non-positive diagonal
+    of the implicit transport equation), the concentration variance every
+    `every` steps and the smallest relative bulk density at the end."""
+    out = []
+    for st_num in stokes:
+        case = make_hit_case(n, seed, mach=mach, stokes=(st_num,))
+        s = P.Solver.from_case(case, p_tol=p_tol, cfl=0.5)
+        first_neg = first_diag = None
+        var = [s.stats()["conc_var"][0]]
+        done, status = 0, 0
+        t0 = time.time()
+        while done < steps:
+            k = min(every, steps - done)
+            st, info = s.step(k, raise_on_error=False)
+            for j, i in enumerate(info):
+                if first_neg is None and i["flags"] & P.FLAG_DUST_NEG:
+                    first_neg = done + j + 1
+                if first_diag is None and i["flags"] & P.FLAG_DUST_DIAG:
+                    first_diag = done + j + 1
+            if st < 0:
+                status = st
+                break
+            done += k
+            var.append(s.stats()["conc_var"][0])
+        rp = s.get(P.FIELD_RHO_P).cpu().numpy()[0]
+        row = dict(stokes=st_num, tau_p=case.tau_p[0], steps=done, status=status,
+                   first_negative_step=first_neg, first_diagonal_step=first_diag,
+                   conc_var_every=var, conc_var_max=float(np.max(var)),
+                   min_rel_density=float(rp.min() / rp.mean()))
+        log(f"St {st_num}: {done} steps in {time.time() - t0:.1f}s, first negative "
+            f"{first_neg}, first diagonal {first_diag}, variance max {row['conc_var_max']:.3g}, "
+            f"min rho_j/<rho_j> {row['min_rel_density']:.3g}")
+        out.append(row)
+        s.close()
+    return dict(n=n, steps=steps, every=every, mach=mach, seed=seed, runs=out)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["precision", "stats"])
+    ap.add_argument("what", choices=["precision", "stats", "stokes"])
+    ap.add_argument("--mach", type=float, default=0.5)
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--every", type=int, default=10)
@@ -118,6 +165,9 @@ def main():
         print(m, file=sys.stderr, flush=True)
     if args.what == "precision":
         r = precision(n=args.n or 256, steps=args.steps or 200, every=args.every, log=log)
+    elif args.what == "stokes":
+        r = stokes_range(n=args.n or 128, steps=args.steps or 500, every=args.every,
+                         mach=args.mach, log=log)
     else:
         r = stats_run(n=args.n or 128, steps=args.steps or 500, every=args.every, log=log)
     text = json.dumps(r)
