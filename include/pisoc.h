@@ -48,7 +48,8 @@ typedef enum {
     PISOC_OK = 0,
     PISOC_WARN_NOT_CONVERGED = 1, /* a pressure solve hit p_maxit (state advanced) */
     PISOC_WARN_GUESS_FALLBACK = 2, /* learned guess rejected, zero guess used */
-    PISOC_WARN_DUST = 3,           /* PISOC_FLAG_DUST_NEG or _DUST_DIAG raised (state advanced) */
+    PISOC_WARN_DUST = 3,           /* PISOC_FLAG_DUST_NEG, _DUST_DIAG or _DUST_COURANT raised
+                                      (state advanced) */
     PISOC_ERR_INVALID = -1,        /* bad argument, or dt undefined/non-positive */
     PISOC_ERR_HIP = -2,            /* a HIP runtime call failed */
     PISOC_ERR_DIVERGED = -3,       /* non-finite or non-positive gas density, non-finite
@@ -88,7 +89,14 @@ enum {
     /* the diagonal rho^{n+1}/dt + (9/16) div G of the implicit mass-ratio
      * equation is <= 0 in some cell: the drift compresses the dust faster than
      * the equation's Jacobi sweeps can follow (PISOC_WARN_DUST) */
-    PISOC_FLAG_DUST_DIAG = 256
+    PISOC_FLAG_DUST_DIAG = 256,
+    /* the dust's Courant number (pisoc_step_info.courant_dust) is >= 0.638: for a
+     * uniform drift the dust update (its 4 Jacobi sweeps and the conservative
+     * finish, the polynomial sum_{l<=5} (-z)^l of the I4 transport symbol z)
+     * amplifies some Fourier mode beyond it.  The time step follows the gas's
+     * Courant number only; the drift tau_j (g - Du/Dt) raises the dust's
+     * (PISOC_WARN_DUST) */
+    PISOC_FLAG_DUST_COURANT = 512
 };
 
 typedef struct {
@@ -144,6 +152,9 @@ typedef struct {
     int32_t flags;                   /* PISOC_FLAG_* */
     double mass_gas;                 /* sum rho V after the step */
     double mass_p[PISOC_MAX_CLASSES];/* sum rho_j V after the step */
+    double courant_dust;             /* max over the classes of sigma_j dt, sigma_j =
+                                        max_P sum_f |G_f| / (2 rho^{n+1} V) with G the
+                                        class's mass flux per unit mass ratio */
 } pisoc_step_info;
 
 typedef struct {

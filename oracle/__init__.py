@@ -24,7 +24,8 @@ MAX_CORR = 8
 
 OK, WARN_NOT_CONVERGED, WARN_DUST, ERR_INVALID, ERR_DIVERGED = 0, 1, 3, -1, -3
 FLAG_PCG_MAXIT, FLAG_NONFINITE, FLAG_RHO_NONPOS, FLAG_KFACE_NONPOS = 1, 2, 4, 8
-FLAG_DUST_NEG, FLAG_DUST_NONFINITE, FLAG_DUST_DIAG = 64, 128, 256
+FLAG_DUST_NEG, FLAG_DUST_NONFINITE, FLAG_DUST_DIAG, FLAG_DUST_COURANT = 64, 128, 256, 512
+DUST_COURANT_MAX = 0.638
 
 RHO, U, PHI, RHO_P, P = 0, 1, 2, 3, 4
 SYS_B, SYS_W, SYS_PSIDT, SYS_K, SYS_X, SYS_P0, SYS_DIAG, SYS_USTAR = 10, 11, 12, 13, 14, 15, 16, 17
@@ -53,7 +54,7 @@ class OraInfo(C.Structure):
         ("t", C.c_double), ("dt", C.c_double), ("courant", C.c_double),
         ("pcg_iters", C.c_int32 * MAX_CORR), ("pcg_relres", C.c_double * MAX_CORR),
         ("flags", C.c_int32), ("mass_gas", C.c_double),
-        ("mass_p", C.c_double * MAX_CLASSES),
+        ("mass_p", C.c_double * MAX_CLASSES), ("courant_dust", C.c_double),
     ]
 
 
@@ -410,7 +411,7 @@ class Oracle:
                             pcg_iters=list(r.pcg_iters[: self.prm.n_corr]),
                             pcg_relres=list(r.pcg_relres[: self.prm.n_corr]),
                             flags=r.flags, mass_gas=r.mass_gas,
-                            mass_p=list(r.mass_p[: self.K])))
+                            mass_p=list(r.mass_p[: self.K]), courant_dust=r.courant_dust))
         return st, out
 
     def get(self, which, corr=0):

@@ -714,6 +714,17 @@ static int one_step(ora_state* s, ora_info* info) {
             for (int d = 0; d < 3; ++d)
                 for (size_t P = 0; P < N; ++P) G[d][P] = phin[d][P] - tau * Dfa[d][P];
             ora_div_flux(n, G[0], G[1], G[2], divG);
+            /* the dust's Courant number, as the gas's with G in place of phi */
+            for (int k = 0; k < n; ++k)
+                for (int j = 0; j < n; ++j)
+                    for (int i = 0; i < n; ++i) {
+                        const size_t P = cell(n, i, j, k);
+                        double f = 0.0;
+                        for (int d = 0; d < 3; ++d)
+                            f += fabs(G[d][P]) + fabs(G[d][shifted(n, i, j, k, d, -1)]);
+                        const double cd = f / (2.0 * rhok[P] * V) * dt;
+                        if (cd > info->courant_dust) info->courant_dust = cd;
+                    }
             /* the diagonal of the implicit equation below must stay positive */
             for (size_t P = 0; P < N; ++P)
                 if (!(rhok[P] / dt + (9.0 / 16.0) * divG[P] > 0.0)) flags |= ORA_FLAG_DUST_DIAG;
@@ -764,10 +775,14 @@ static int one_step(ora_state* s, ora_info* info) {
     info->courant = sigma * dt;
     info->flags = flags;
     info->mass_gas = m_gas;
+    if (!(info->courant_dust < ORA_DUST_COURANT_MAX) && pr->n_classes > 0)
+        flags |= ORA_FLAG_DUST_COURANT;
+    info->flags = flags;
     if (flags & (ORA_FLAG_NONFINITE | ORA_FLAG_RHO_NONPOS | ORA_FLAG_DUST_NONFINITE)) {
         status = ORA_ERR_DIVERGED;
     } else {
-        if ((flags & (ORA_FLAG_DUST_NEG | ORA_FLAG_DUST_DIAG)) && status == ORA_OK)
+        if ((flags & (ORA_FLAG_DUST_NEG | ORA_FLAG_DUST_DIAG | ORA_FLAG_DUST_COURANT)) &&
+            status == ORA_OK)
             status = ORA_WARN_DUST;
         memcpy(s->rho, rhok, N * sizeof(double));
         for (int d = 0; d < 3; ++d) {

@@ -43,6 +43,12 @@ extern "C" {
 /* the implicit mass-ratio equation's diagonal rho^{n+1}/dt + (9/16) div G is
  * <= 0 in some cell (its Jacobi sweeps lose their contraction there; warning) */
 #define ORA_FLAG_DUST_DIAG 256
+/* the dust's Courant number sigma_j dt, sigma_j = max sum_f |G_f| / (2 rho V), is
+ * >= 0.638 for some class: for a uniform drift the update (n_Y = 4 Jacobi sweeps
+ * and the conservative finish, the polynomial sum_{l<=5} (-z)^l of the central
+ * I4 transport symbol z) amplifies some Fourier mode beyond that (warning) */
+#define ORA_FLAG_DUST_COURANT 512
+#define ORA_DUST_COURANT_MAX 0.638
 
 typedef struct {
     int32_t n;
@@ -68,6 +74,7 @@ typedef struct {
     int32_t flags;
     double mass_gas;
     double mass_p[ORA_MAX_CLASSES];
+    double courant_dust;   /* max over the classes of sigma_j dt */
 } ora_info;
 
 /* statistics, in this order */

@@ -76,6 +76,8 @@ struct DevState {
     // two-way coupling: mean mixture density <rho + sum_j rho_j> (a constant of
     // the run: gas and dust masses are conserved exactly)
     double rhom_mean;
+    // the dust's Courant number of the step (max over the classes)
+    double courant_dust;
 };
 
 // A cell and the periodic offsets to the cells up to two steps away along

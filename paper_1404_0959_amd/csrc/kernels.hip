@@ -35,6 +35,12 @@ namespace pisoc {
 
 __host__ __device__ static inline size_t ncell(const Phys& ph) { return ph.NT; }
 
+// Largest dust Courant number at which the dust update (4 Jacobi sweeps and the
+// conservative finish) damps every Fourier mode of a uniform drift: the root
+// y = 0.8130 of (1 + y^6)^2 = 1 + y^2 over the I4 transport symbol's maximum
+// 1.2739.
+constexpr double kDustCourantMax = 0.638;
+
 // ---------------------------------------------------------------- utilities
 template <typename T>
 __global__ void k_cast_in(const double* __restrict__ src, T* __restrict__ dst, size_t count,
@@ -1931,8 +1937,9 @@ __device__ inline T dust_sweep_cell(const T (&yv)[13], const T (&gpv)[3], const 
     return (rj / dt - off) / diag;
 }
 
-// CHECK (a class's first sweep; the diagonal is the same in every sweep):
-// partials of max(-diagonal), so that a diagonal <= 0 anywhere is flagged.
+// CHECK (a class's first sweep; the diagonal and G are the same in every
+// sweep): partials of max(-diagonal), so that a diagonal <= 0 anywhere is
+// flagged, and of the dust's Courant rate sum_f |G_f| / (2 rho^{n+1} V).
 template <typename T, bool CHECK>
 __global__ void __launch_bounds__(kBlock) k_dust_sweep(Phys ph, const DevState* st,
                                                        const T* __restrict__ Yin, T* __restrict__ Yout,
@@ -1941,7 +1948,8 @@ __global__ void __launch_bounds__(kBlock) k_dust_sweep(Phys ph, const DevState* 
     MEMBER(ph)
     const size_t N = ncell(ph);
     const T dt = (T)(st + mem_)->dt, inv_V = (T)ph.inv_V;
-    double v[1] = {-__builtin_inf()};
+    double v[2] = {-__builtin_inf(), 0.0};
+    const double rref = (st + mem_)->rho_ref;
     FOR_CELLS(ph)
     T yv[13], gpv[3], gmv[3];
     gather13(Yin, c, yv);
@@ -1954,9 +1962,12 @@ __global__ void __launch_bounds__(kBlock) k_dust_sweep(Phys ph, const DevState* 
     loads_issued();
     T dg;
     Yout[P] = dust_sweep_cell(yv, gpv, gmv, rj, r1P, dt, inv_V, (T)(st + mem_)->rho_ref, dg);
-    if (CHECK) v[0] = fmax(v[0], -(double)dg);
+    if (CHECK) {
+        v[0] = fmax(v[0], -(double)dg);
+        v[1] = fmax(v[1], courant_rate(gpv, gmv, r1P, rref, ph.V));
+    }
     END_CELLS
-    if (CHECK) block_partials<1, 1u>(v, part);
+    if (CHECK) block_partials<2, 3u>(v, part);
 }
 
 // Face dust mass fluxes F = G I4(Y), overwriting G on own faces.
@@ -2069,7 +2080,10 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(const double* part, uns
 // and the dust class masses from the partials of the last corrector and of
 // the dust finish, and the dust flags: 64 some rho_j < 0, 128 a non-finite
 // rho_j (the sum is then non-finite), 256 the implicit diagonal <= 0 in some
-// cell (from the first sweep's maxima of -diagonal).
+// cell (from the first sweep's maxima of -diagonal), 512 the dust's Courant
+// number (the first sweep's maxima of its rate, times dt) at or above
+// kDustCourantMax, beyond which the transport update amplifies some Fourier
+// mode of a uniform drift.
 __global__ void __launch_bounds__(kBlock) k_step_finish(Phys ph, DevState* st,
                                                         const double* part_mass, unsigned nb_mass,
                                                         const double* part_dust, int ncls,
@@ -2086,16 +2100,21 @@ __global__ void __launch_bounds__(kBlock) k_step_finish(Phys ph, DevState* st,
         if (!isfinite(v[0]) || !isfinite(v[1])) sm->flags |= 2;
         if (!(-v[2] > 0.0)) sm->flags |= 4;
     }
+    if (flat_tid() == 0) sm->courant_dust = 0.0;
     for (int c = 0; c < ncls; ++c) {
-        // columns nb_dust apart: sum rho_j, max(-rho_j)
-        double mm[2], dg[1];
+        // columns nb_dust apart: sum rho_j, max(-rho_j); nb_diag apart:
+        // max(-diagonal), max Courant rate
+        double mm[2], dg[2];
         reduce_member<2, 2u>(part_dust + (size_t)(2 * c) * cls_stride, nb_dust, ph.batch, m, mm);
-        reduce_member<1, 1u>(part_diag + (size_t)c * cls_stride, nb_diag, ph.batch, m, dg);
+        reduce_member<2, 3u>(part_diag + (size_t)(2 * c) * cls_stride, nb_diag, ph.batch, m, dg);
         if (flat_tid() == 0) {
             sm->mass_p[c] = mm[0] * ph.V;
             if (!isfinite(mm[0])) sm->flags |= 128;
             else if (mm[1] > 0.0) sm->flags |= 64;
             if (!(dg[0] < 0.0)) sm->flags |= 256;
+            const double cd = dg[1] * sm->dt;
+            if (cd > sm->courant_dust) sm->courant_dust = cd;
+            if (!(cd < kDustCourantMax)) sm->flags |= 512;
         }
     }
 }
@@ -2681,25 +2700,33 @@ template <typename T, bool CHECK>
 struct TiledDustSweep : TiledBase<T> {
     static constexpr int NS = 1;          // Y_in
     static constexpr bool FACES = true;   // G
-    static constexpr int NR = CHECK ? 1 : 0;   // max(-diagonal), as k_dust_sweep
-    static constexpr unsigned MASK = 1u;
+    static constexpr int NR = CHECK ? 2 : 0;   // max(-diagonal), Courant rate, as k_dust_sweep
+    static constexpr unsigned MASK = 3u;
     const T* sf[1];
     const T *rhoj, *r1;
     T* Yout;
     T dt, inv_V, rref;
+    double Vc;
     struct Pts { T rj, r1; };
     __device__ void member(const Phys& ph, const DevState* d) {
         dt = (T)d->dt;
         inv_V = (T)ph.inv_V;
         rref = (T)d->rho_ref;
+        Vc = ph.V;
     }
     __device__ Pts load(size_t P) const { return {stream_ld(rhoj + P), stream_ld(r1 + P)}; }
-    __device__ void init(double* acc) const { acc[0] = -__builtin_inf(); }
+    __device__ void init(double* acc) const {
+        acc[0] = -__builtin_inf();
+        if (CHECK) acc[1] = 0.0;
+    }
     __device__ void cell(size_t P, const T (&v)[1][13], const T (&fp)[3], const T (&fm)[3],
                          const Pts& p, double* acc) const {
         T dg;
         stream_st(Yout + P, dust_sweep_cell(v[0], fp, fm, p.rj, p.r1, dt, inv_V, rref, dg));
-        if (CHECK) acc[0] = fmax(acc[0], -(double)dg);
+        if (CHECK) {
+            acc[0] = fmax(acc[0], -(double)dg);
+            acc[1] = fmax(acc[1], courant_rate(fp, fm, p.r1, (double)rref, Vc));
+        }
     }
 };
 

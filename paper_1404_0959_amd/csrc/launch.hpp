@@ -65,10 +65,11 @@ enum PartSlot {
     // 2 kMaxClasses columns: class c's dust finish writes, from PS_DUST + 2c
     // on, columns of nb partials each: sum rho_j, then max(-rho_j)
     PS_DUST = PS_STAT + 4,
-    // kMaxClasses columns: max(-diagonal) of class c's implicit equation, from
-    // its first sweep
+    // 2 kMaxClasses columns: class c's first sweep writes, from PS_DDIAG + 2c
+    // on, columns of nb partials each: max(-diagonal) of its implicit
+    // equation, then its maximal Courant rate sum_f |G_f| / (2 rho V)
     PS_DDIAG = PS_DUST + 2 * kMaxClasses,
-    PS_COLUMNS = PS_DDIAG + kMaxClasses
+    PS_COLUMNS = PS_DDIAG + 2 * kMaxClasses
 };
 
 // Operands of CG iteration k.  Reads r_{k-1}, p_{k-1}, q_{k-1} (rin, pold,
@@ -168,7 +169,8 @@ struct Ops {
                           const DevState* st, int cls, const T* phi, const T* r1, const T* acc,
                           T* G, const T* rhoj, const T* rn, T* Y);
     // part_diag non-null (the class's first sweep): partials max(-diagonal)
-    // of the implicit equation; returns the launch's block count
+    // of the implicit equation and max of the dust's Courant rate (two
+    // columns of the launch's block count); returns the launch's block count
     static unsigned dust_sweep(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
                                const DevState* st, const T* Yin, T* Yout, const T* G,
                                const T* rhoj, const T* r1, double* part_diag);
@@ -227,7 +229,7 @@ void sum_partials(hipStream_t s, const double* part, unsigned nb, double* dst);
 // Per member: end-of-step mass budget and flags.
 // nb_mass: partials of the last corrector update; nb_dust: of the dust finish
 // (class c's two columns from part_dust + 2 c cls_stride); nb_diag: of the
-// first dust sweep (class c's column at part_diag + c cls_stride)
+// first dust sweep (class c's two columns from part_diag + 2 c cls_stride)
 void step_finish(hipStream_t s, const Phys& ph, DevState* st, const double* part_mass,
                  unsigned nb_mass, const double* part_dust, int ncls, unsigned nb_dust,
                  const double* part_diag, unsigned nb_diag, size_t cls_stride);

@@ -728,7 +728,7 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
             T* yout = S.Yb;
             for (int i = 0; i < p.n_dust_sweeps; ++i) {
                 // the first sweep also checks the implicit diagonal (the same in every sweep)
-                double* chk = i == 0 ? ctx->part(PS_DDIAG + c) : nullptr;
+                double* chk = i == 0 ? ctx->part(PS_DDIAG + 2 * c) : nullptr;
                 timed(ctx, KC_DUST_SWEEP, 7, -1, [&] {
                     const unsigned nb =
                         O::dust_sweep(L, ctx->TL, s, ph, st, yin, yout, S.G, S.rj + c * N, S.rk, chk);
@@ -1045,6 +1045,7 @@ void fill_info(const pisoc_ctx* ctx, const DevState& h, bool committed, pisoc_st
         rec.refinements[c] = h.rounds_corr[c];
     }
     for (int c = 0; c < ctx->prm.n_classes; ++c) rec.mass_p[c] = h.mass_p[c];
+    rec.courant_dust = h.courant_dust;
     *out = rec;
 }
 
@@ -1058,7 +1059,8 @@ bool member_bad(const pisoc_ctx* ctx, const DevState& h) {
 
 pisoc_status flag_status(int flags) {
     if (flags & PISOC_FLAG_PCG_MAXIT) return PISOC_WARN_NOT_CONVERGED;
-    if (flags & (PISOC_FLAG_DUST_NEG | PISOC_FLAG_DUST_DIAG)) return PISOC_WARN_DUST;
+    if (flags & (PISOC_FLAG_DUST_NEG | PISOC_FLAG_DUST_DIAG | PISOC_FLAG_DUST_COURANT))
+        return PISOC_WARN_DUST;
     if (flags & PISOC_FLAG_GUESS_FALLBACK) return PISOC_WARN_GUESS_FALLBACK;
     return PISOC_OK;
 }

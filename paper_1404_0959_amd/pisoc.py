@@ -22,7 +22,7 @@ FP64, FP32_REFINED = 0, 1
 GUESS_ZERO, GUESS_LEARNED, GUESS_PREVIOUS = 0, 1, 2
 FLAG_PCG_MAXIT, FLAG_NONFINITE, FLAG_RHO_NONPOS, FLAG_GUESS_FALLBACK, FLAG_BAD_DT = 1, 2, 4, 8, 16
 FLAG_GUESS_SKIPPED = 32
-FLAG_DUST_NEG, FLAG_DUST_NONFINITE, FLAG_DUST_DIAG = 64, 128, 256
+FLAG_DUST_NEG, FLAG_DUST_NONFINITE, FLAG_DUST_DIAG, FLAG_DUST_COURANT = 64, 128, 256, 512
 
 FIELD_RHO, FIELD_U, FIELD_PHI, FIELD_RHO_P, FIELD_P = 1, 2, 4, 8, 16
 FIELD_PSOLVE_B, FIELD_PSOLVE_X, FIELD_P_PREV, FIELD_PSOLVE_DIAG = 32, 64, 128, 256
@@ -72,7 +72,7 @@ class StepInfo(C.Structure):
         ("pcg_iters", C.c_int32 * MAX_CORR), ("pcg_relres", C.c_double * MAX_CORR),
         ("refinements", C.c_int32 * MAX_CORR),
         ("flags", C.c_int32), ("mass_gas", C.c_double),
-        ("mass_p", C.c_double * MAX_CLASSES),
+        ("mass_p", C.c_double * MAX_CLASSES), ("courant_dust", C.c_double),
     ]
 
 
@@ -353,7 +353,8 @@ class Solver:
 def _info_dict(r, nc, K):
     return dict(t=r.t, dt=r.dt, courant=r.courant, pcg_iters=list(r.pcg_iters[:nc]),
                 pcg_relres=list(r.pcg_relres[:nc]), refinements=list(r.refinements[:nc]),
-                flags=r.flags, mass_gas=r.mass_gas, mass_p=list(r.mass_p[:K]))
+                flags=r.flags, mass_gas=r.mass_gas, mass_p=list(r.mass_p[:K]),
+                courant_dust=r.courant_dust)
 
 
 class Ensemble:

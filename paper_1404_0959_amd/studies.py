@@ -21,7 +21,8 @@ enstrophy, density and Mach r.m.s., concentration variance per class and the
 gas and dust mass budgets.
 
 stokes: one run per Stokes number at 128^3 (default Mach 0.5): when the dust
-flags first rise (negative bulk density, non-positive implicit diagonal),
+flags first rise (negative bulk density, non-positive implicit diagonal, the
+dust's Courant number past the transport update's stability bound),
 the concentration variance over time and the smallest relative dust density,
 which bound the Stokes range where the transport reading stays usable.
 """
@@ -121,7 +122,8 @@ def stokes_range(n=128, steps=500, every=10, seed=0, p_tol=1e-8, mach=0.5,
     for st_num in stokes:
         case = make_hit_case(n, seed, mach=mach, stokes=(st_num,))
         s = P.Solver.from_case(case, p_tol=p_tol, cfl=0.5)
-        first_neg = first_diag = None
+        first_neg = first_diag = first_courant = None
+        cmax = 0.0
         var = [s.stats()["conc_var"][0]]
         done, status = 0, 0
         t0 = time.time()
@@ -133,6 +135,9 @@ def stokes_range(n=128, steps=500, every=10, seed=0, p_tol=1e-8, mach=0.5,
                     first_neg = done + j + 1
                 if first_diag is None and i["flags"] & P.FLAG_DUST_DIAG:
                     first_diag = done + j + 1
+                if first_courant is None and i["flags"] & P.FLAG_DUST_COURANT:
+                    first_courant = done + j + 1
+                cmax = max(cmax, i["courant_dust"])
             if st < 0:
                 status = st
                 break
@@ -141,10 +146,12 @@ def stokes_range(n=128, steps=500, every=10, seed=0, p_tol=1e-8, mach=0.5,
         rp = s.get(P.FIELD_RHO_P).cpu().numpy()[0]
         row = dict(stokes=st_num, tau_p=case.tau_p[0], steps=done, status=status,
                    first_negative_step=first_neg, first_diagonal_step=first_diag,
+                   first_dust_courant_step=first_courant, dust_courant_max=cmax,
                    conc_var_every=var, conc_var_max=float(np.max(var)),
                    min_rel_density=float(rp.min() / rp.mean()))
         log(f"St {st_num}: {done} steps in {time.time() - t0:.1f}s, first negative "
-            f"{first_neg}, first diagonal {first_diag}, variance max {row['conc_var_max']:.3g}, "
+            f"{first_neg}, first diagonal {first_diag}, first dust Courant >= 0.638 "
+            f"{first_courant} (max {cmax:.3f}), variance max {row['conc_var_max']:.3g}, "
             f"min rho_j/<rho_j> {row['min_rel_density']:.3g}")
         out.append(row)
         s.close()

@@ -149,8 +149,8 @@ def test_helm_solve_edges(P, ora):
 
 # ------------------------------------------------------------ whole step
 # step flags both sides define alike: solve cap, non-finite / non-positive gas,
-# and the three dust flags
-SHARED_FLAGS = 1 | 2 | 4 | 64 | 128 | 256
+# and the four dust flags
+SHARED_FLAGS = 1 | 2 | 4 | 64 | 128 | 256 | 512
 
 
 def run_pair(P, ora, case, steps, **kw):
@@ -165,6 +165,7 @@ def run_pair(P, ora, case, steps, **kw):
     for a, b in zip(info_o, info_g):
         assert a["pcg_iters"] == b["pcg_iters"], (a, b)
         assert a["flags"] & SHARED_FLAGS == b["flags"] & SHARED_FLAGS, (a["flags"], b["flags"])
+        assert abs(a["courant_dust"] - b["courant_dust"]) <= 1e-10 * max(a["courant_dust"], 1e-300)
         assert abs(a["dt"] - b["dt"]) <= 1e-10 * a["dt"]
         assert abs(a["mass_gas"] - b["mass_gas"]) <= 1e-12 * a["mass_gas"]
     return o, s, info_o, info_g
@@ -489,3 +490,28 @@ def test_dust_flags_as_oracle(P, ora, precision):
         stg, ig = g.step(1)
         assert bool(ig[0]["flags"] & P.FLAG_DUST_DIAG) == flagged
         assert io[0]["flags"] & 256 == ig[0]["flags"] & 256
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dust_courant_as_oracle(P, ora, precision):
+    """The dust's Courant number of settling dust is tau g dt / h exactly, and
+    its flag (512) rises from 0.638 on, as in the oracle."""
+    kw = {} if precision == "fp64" else dict(precision=P.FP32_REFINED, inner_tol=1e-7)
+    n, dt, g0 = 16, 0.1, 1.0
+    h = 2 * math.pi / n
+    x, y, z = grid(n)
+    rho = np.ones((n, n, n))
+    u = np.zeros((3, n, n, n))
+    rp = (1e-3 * (1 + 0.01 * np.sin(4 * z)))[None]
+    for c in (0.5, 0.7):
+        tau = c * h / (g0 * dt)
+        args = dict(gamma=1.4, C_=10.0, mu=1e-3, tau_p=(tau,), dt_fixed=dt,
+                    gravity=(0.0, 0.0, -g0))
+        o = ora.Oracle(n, rho, u, rp, p_tol=1e-12, **args)
+        g = P.Solver(n, rho, u, rp, p_tol=1e-12 if precision == "fp64" else 1e-7, **args, **kw)
+        sto, io = o.step(2)
+        stg, ig = g.step(2)
+        tol = 1e-12 if precision == "fp64" else 1e-6
+        for a, b in zip(io, ig):
+            assert abs(b["courant_dust"] - c) <= tol and abs(a["courant_dust"] - c) <= 1e-12
+            assert a["flags"] & 512 == b["flags"] & 512 == (512 if c >= 0.638 else 0)

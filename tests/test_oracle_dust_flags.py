@@ -86,3 +86,31 @@ def test_diagonal_flag_threshold(ora, factor, flagged):
     assert bool(info[0]["flags"] & ora.FLAG_DUST_DIAG) == flagged, info[0]["flags"]
     if flagged:
         assert st == ora.WARN_DUST
+
+
+def test_dust_courant_number_and_flag(ora):
+    """Dust settling through gas at rest: G = -tau g rho A on every z-face, so
+    the dust's Courant number sum_f |G_f| dt / (2 rho V) is tau g dt / h
+    exactly.  Beyond 0.638 the transport's amplification of a uniform drift
+    exceeds 1 for some Fourier mode (the root of (1 + y^6)^2 = 1 + y^2,
+    y = 0.8130, over the symbol's maximum 1.2739): the flag (512, warning)
+    rises there, and the settled dust mode grows instead of decaying."""
+    n, dt, g0 = 16, 0.1, 1.0
+    h = 2 * math.pi / n
+    x, y, z = grid(n)[1]
+    rho = np.ones((n, n, n))
+    u = np.zeros((3, n, n, n))
+    k = 4      # near the symbol's maximum: (20 sin kh - 2 sin 2kh)/16 at kh = pi/2
+    rp = (1e-3 * (1 + 0.01 * np.sin(k * z)))[None]
+    amps = {}
+    for c in (0.5, 0.7):
+        tau = c * h / (g0 * dt)
+        o = ora.Oracle(n, rho, u, rp, gamma=1.4, C_=10.0, mu=1e-3, tau_p=(tau,), dt_fixed=dt,
+                       p_tol=1e-12, gravity=(0.0, 0.0, -g0))
+        st, info = o.step(3)
+        assert abs(info[0]["courant_dust"] - c) < 1e-12
+        flagged = bool(info[0]["flags"] & ora.FLAG_DUST_COURANT)
+        assert flagged == (c >= ora.DUST_COURANT_MAX)
+        d = o.get(ora.RHO_P)[0] / 1e-3 - 1
+        amps[c] = np.max(np.abs(d)) / 0.01
+    assert amps[0.5] < 1.0 < amps[0.7], amps
