@@ -252,6 +252,25 @@ def extras_run(P, torch, case, args):
     E, lam, D = P.spectrum(u)
     diag["taylor_microscale"] = lam
     out["diagnostics"] = diag
+    del u
+    # the learned guess's network alone on one n^3 input (seeded normal):
+    # forward (30,240 BF16 flops per cell; 204 bytes per cell of activations
+    # read and written once, layer by layer) and one training gradient
+    from paper_1404_0959_amd.learn import load_weights
+    w = load_weights()
+    g = torch.Generator(device="cuda").manual_seed(args.seed)
+    x = torch.randn(1, n3, 2, generator=g, device="cuda")
+    net = P.Net(args.n, 1)
+    t_fwd = time_it(lambda: net.forward(w, x))
+    flop, bpc = 30240 * n3, 204
+    out["net"] = dict(forward_ms=round(t_fwd * 1e3, 3), forward_tflops=round(flop / t_fwd / 1e12, 1),
+                      forward_frac_bf16_peak=round(flop / t_fwd / 2.5e15, 4),
+                      forward_gbs=round(bpc * n3 / t_fwd / 1e9, 1),
+                      forward_frac_hbm=round(bpc * n3 / t_fwd / 8e12, 4))
+    t_grad = time_it(lambda: net.grad(w, x, x[..., 0].contiguous()))
+    out["net"]["grad_ms"] = round(t_grad * 1e3, 3)
+    log(f"network forward: {t_fwd * 1e3:.3f} ms ({flop / t_fwd / 1e12:.0f} TFLOP/s), "
+        f"gradient {t_grad * 1e3:.3f} ms")
     return out
 
 

@@ -25,6 +25,8 @@ namespace pisoc {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 __device__ inline float bf2f(uint16_t b) {
     uint32_t u = (uint32_t)b << 16;
@@ -113,21 +115,56 @@ __global__ void __launch_bounds__(256) k_conv(int n, int batch, const uint16_t* 
 
 // Forward pass of a 16-input-channel layer with input reuse across output
 // rows.  A wavefront owns 16 cells along x of a block of kRY x kRZ output rows
-// (y, z).  It walks the (kRY + 2) x (kRZ + 2) input rows that block touches;
-// each input row, taken at the three x shifts, is loaded once (8 bytes per
-// lane: 4 channels of one cell) and fed to the matrix cores for every output
-// row and tap it contributes to -- 432 products per 108 loads, where the
-// row-at-a-time kernel issues one load per product.  Output: 16 BF16
-// channels per cell (ReLU when relu is set).
+// (y, z) and walks the (kRY + 2) x (kRZ + 2) input rows that block touches,
+// each loaded once and fed to the matrix cores for every output row and tap
+// it contributes to.
 constexpr int kRY = 4, kRZ = 4;
 // input rows whose loads are in flight ahead of the products that use them
-// (at occupancy 2 the registers allow it; 8 measured fastest of 2, 4, 6, 8)
+// (for the first and last layers; 8 measured fastest of 2, 4, 6, 8)
 constexpr int kAhead = 8;
 
-__global__ void __launch_bounds__(256) k_conv16_rows(int n, int batch,
-                                                     const uint16_t* __restrict__ in,
-                                                     const v4s* __restrict__ wpk, int relu,
-                                                     uint16_t* __restrict__ out) {
+// The 16 -> 16 layers run on gfx950's K = 32 product
+// (v_mfma_f32_16x16x32_bf16, twice the work of the K = 16 form per issue).
+// Within one input plane the (kRY + 2) x 3 (row, x shift) items r = 3 iy + q
+// are taken two at a time: pair p holds item 2p in lane groups 0-1 and item
+// 2p + 1 in groups 2-3, 8 channels (16 bytes) of one cell per lane.  Output row
+// oy reads items 3 oy .. 3 oy + 8, the 5 pairs from floor(3 oy / 2) on, whose
+// weight operand depends only on the parity c of oy, the pair's slot s in that
+// run and dz: 30 operands, held in registers.  240 products per tile of
+// 16 x kRY x kRZ cells (432 with K = 16), 10 % of their entries the zero
+// halves at the ends of odd and even runs.
+constexpr int kItems = 3 * (kRY + 2), kPairs = kItems / 2, kSlots = 5;
+static_assert(kItems % 2 == 0, "items pair up within a plane");
+
+// Output of a tile computed as D^T (weights as the A operand): lane (g, m)
+// holds channels 4g..4g+3 of cell x of each output row, stored as one 8-byte
+// BF16 quad (ReLU when relu is set).
+__device__ inline void store_rows(const v4f (&acc)[kRY][kRZ], uint16_t* __restrict__ out, int n,
+                                  int x, int j0, int k0, int g, int relu) {
+#pragma unroll
+    for (int oz = 0; oz < kRZ; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < kRY; ++oy) {
+            const size_t cell = (size_t)x + (size_t)n * ((size_t)(j0 + oy) + (size_t)n * (k0 + oz));
+            v4s q;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float v = acc[oy][oz][e];
+                q[e] = (short)f2bf(relu && !(v > 0.f) ? 0.f : v);
+            }
+            *reinterpret_cast<v4s*>(out + cell * 16 + 4 * g) = q;
+        }
+}
+
+__device__ inline v4f mfma_k32(v8s a, v8s b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                   __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
+
+__global__ void __launch_bounds__(256) k_conv16_pairs(int n, int batch,
+                                                      const uint16_t* __restrict__ in,
+                                                      const v8s* __restrict__ wpp, int relu,
+                                                      uint16_t* __restrict__ out) {
     const int lane = threadIdx.x & 63;
     const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int segs = n / 16, nyb = n / kRY, nzb = n / kRZ;
@@ -140,88 +177,75 @@ __global__ void __launch_bounds__(256) k_conv16_rows(int n, int batch,
     const int k0 = (int)(rest % nzb) * kRZ;
     const int b = (int)(rest / nzb);
     const size_t N = (size_t)n * n * n;
-    const int m = lane & 15, g = lane >> 4;
-    v4s B[27];
+    const int m = lane & 15, g = lane >> 4, h = g >> 1;
+    v8s B[2][kSlots][3];
 #pragma unroll
-    for (int t = 0; t < 27; ++t) B[t] = wpk[t * 64 + lane];
-    // keep the weights in registers for the whole tile (the compiler would
-    // otherwise reload each one next to its products)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int t = 0; t < 27; ++t) asm volatile("" : "+v"(B[t]));
+        for (int s = 0; s < kSlots; ++s)
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz) B[c][s][dz] = wpp[((c * kSlots + s) * 3 + dz) * 64 + lane];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s)
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz) asm volatile("" : "+v"(B[c][s][dz]));
     v4f acc[kRY][kRZ];
 #pragma unroll
     for (int oy = 0; oy < kRY; ++oy)
 #pragma unroll
         for (int oz = 0; oz < kRZ; ++oz) acc[oy][oz] = v4f{0.f, 0.f, 0.f, 0.f};
-    const uint16_t* inb = in + (size_t)b * N * 16 + 4 * g;
-    int xo[3];
+    // this lane's cell of each pair within a plane (item 2p + h)
+    int off[kPairs];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) xo[q] = wrapn(iseg * 16 + m + q - 1, n);
-    // the (kRY + 2) x (kRZ + 2) input rows in z-major order; each row's three
-    // x-shifted loads are issued kAhead rows ahead of the products that use
-    // them (all loops fully unrolled: every row, tap and buffer index is a
-    // constant)
-    constexpr int kRW = kRY + 2, kRows = kRW * (kRZ + 2);
-    auto load_row = [&](int rrow, v4s (&a)[3]) {
-        const int iz = rrow / kRW, iy = rrow % kRW;
-        const size_t row = (size_t)n * ((size_t)wrapn(j0 - 1 + iy, n) + (size_t)n * wrapn(k0 - 1 + iz, n));
-#pragma clang loop unroll(full)
-        for (int q = 0; q < 3; ++q) a[q] = *reinterpret_cast<const v4s*>(inb + (row + xo[q]) * 16);
-    };
-    v4s abuf[kAhead + 1][3];
-#pragma clang loop unroll(full)
-    for (int r = 0; r < kAhead; ++r) load_row(r, abuf[r]);
-#pragma clang loop unroll(full)
-    for (int iz = 0; iz < kRZ + 2; ++iz) {
-#pragma clang loop unroll(full)
-        for (int iy = 0; iy < kRW; ++iy) {
-            const int rrow = iz * kRW + iy;
-            if (rrow + kAhead < kRows) load_row(rrow + kAhead, abuf[(rrow + kAhead) % (kAhead + 1)]);
-            __builtin_amdgcn_sched_barrier(0);
-#pragma clang loop unroll(full)
-            for (int q = 0; q < 3; ++q) {   // x shift dx = q - 1
-                const v4s a = abuf[rrow % (kAhead + 1)][q];
-#pragma clang loop unroll(full)
-                for (int oz = 0; oz < kRZ; ++oz) {
-                    const int dz = iz - 1 - oz;
-                    if (dz < -1 || dz > 1) continue;
-#pragma clang loop unroll(full)
-                    for (int oy = 0; oy < kRY; ++oy) {
-                        const int dy = iy - 1 - oy;
-                        if (dy < -1 || dy > 1) continue;
-                        const int tap = (dz + 1) * 9 + (dy + 1) * 3 + q;
-                        acc[oy][oz] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, B[tap], acc[oy][oz], 0, 0, 0);
-                    }
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
+    for (int p = 0; p < kPairs; ++p) {
+        const int r = 2 * p + h, iy = r / 3, q = r % 3;
+        off[p] = n * wrapn(j0 - 1 + iy, n) + wrapn(iseg * 16 + m + q - 1, n);
     }
-    // lane holds D[4g + e][lane & 15] of each output row
-    const int nn = lane & 15;
-#pragma unroll
-    for (int oz = 0; oz < kRZ; ++oz)
-#pragma unroll
-        for (int oy = 0; oy < kRY; ++oy)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const size_t cell = (size_t)(iseg * 16 + 4 * g + e) +
-                                    (size_t)n * ((size_t)(j0 + oy) + (size_t)n * (k0 + oz));
-                float v = acc[oy][oz][e];
-                if (relu) v = v > 0.f ? v : 0.f;
-                out[((size_t)b * N + cell) * 16 + nn] = f2bf(v);
+    const uint16_t* inb = in + (size_t)b * N * 16 + 8 * (g & 1);
+    // 4 pairs in flight keeps the kernel at 2 waves per SIMD (measured faster
+    // than 6 or 9 at 1 wave)
+    constexpr int kLoads = (kRZ + 2) * kPairs, kAh = 4;
+    auto load = [&](int t, v8s& a) {
+        const size_t plane = (size_t)n * n * wrapn(k0 - 1 + t / kPairs, n);
+        a = *reinterpret_cast<const v8s*>(inb + (plane + off[t % kPairs]) * 16);
+    };
+    v8s abuf[kAh + 1];
+#pragma clang loop unroll(full)
+    for (int t = 0; t < kAh; ++t) load(t, abuf[t]);
+#pragma clang loop unroll(full)
+    for (int t = 0; t < kLoads; ++t) {
+        const int iz = t / kPairs, p = t % kPairs;
+        if (t + kAh < kLoads) load(t + kAh, abuf[(t + kAh) % (kAh + 1)]);
+        __builtin_amdgcn_sched_barrier(0);
+        const v8s a = abuf[t % (kAh + 1)];
+#pragma clang loop unroll(full)
+        for (int oz = 0; oz < kRZ; ++oz) {
+            const int dz = iz - 1 - oz;
+            if (dz < -1 || dz > 1) continue;
+#pragma clang loop unroll(full)
+            for (int oy = 0; oy < kRY; ++oy) {
+                const int s = p - (3 * oy) / 2;
+                if (s < 0 || s >= kSlots) continue;
+                acc[oy][oz] = mfma_k32(B[oy & 1][s][dz + 1], a, acc[oy][oz]);
             }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    store_rows(acc, out + (size_t)b * N * 16, n, iseg * 16 + m, j0, k0, g, relu);
 }
 
 // Last layer (16 inputs, 1 output): the kRY x kRZ = 16 output rows of the block
-// are the 16 matrix columns, so one product per input row and x shift covers
-// them all (108 products per tile instead of 432 with 15 of 16 columns idle).
-// For input row (iy, iz) at x shift dx = q - 1 the B operand is
-// B[ci][n] = W[ci][tap(dx, iy - 1 - oy, iz - 1 - oz)] for output row
-// n = oy + kRY oz, zero where the offset is out of reach.  The block keeps W in
-// LDS on a zero-padded (dz, dy) grid of [-4, 4]^2, so every lane reads its B
-// operand at its own base plus a compile-time offset.  A is the input row as in
-// k_conv16_rows.  y = yscale * output, FP32.
+// are the 16 matrix rows of the weight operand, so one product per input row
+// and x shift covers them all (108 products per tile instead of 432 with 15 of
+// 16 output channels idle).  For input row (iy, iz) at x shift dx = q - 1 the
+// weight operand is W'[n][ci] = W[ci][tap(dx, iy - 1 - oy, iz - 1 - oz)] for
+// output row n = oy + kRY oz, zero where the offset is out of reach.  The block
+// keeps W in LDS on a zero-padded (dz, dy) grid of [-4, 4]^2, so every lane
+// reads its operand at its own base plus a compile-time offset.  The other
+// operand is the input row, 4 channels of one cell per lane.
+// y = yscale * output, FP32.
 constexpr int kPadW = 9;   // dy, dz in [-4, 4]
 __global__ void __launch_bounds__(256) k_conv16_final_rows(int n, int batch,
                                                            const uint16_t* __restrict__ in,
@@ -275,16 +299,18 @@ __global__ void __launch_bounds__(256) k_conv16_final_rows(int n, int batch,
         const int iz = rrow / kRW, iy = rrow % kRW;
 #pragma clang loop unroll(full)
         for (int q = 0; q < 3; ++q)
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(abuf[rrow % (kAhead + 1)][q],
-                                                            wbase[((iz * kPadW + iy) * 3 + q) * 4],
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wbase[((iz * kPadW + iy) * 3 + q) * 4],
+                                                            abuf[rrow % (kAhead + 1)][q],
                                                             acc, 0, 0, 0);
         __builtin_amdgcn_sched_barrier(0);
     }
-    // lane holds D[4g + e][lane & 15]: cell 4g + e of output row lane & 15
+    // computed as D^T (weights as the A operand): lane (g, m) holds cell m of
+    // output rows 4g + e, so each store covers 16 consecutive cells of 4 rows
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const size_t cell = (size_t)(iseg * 16 + 4 * g + e) +
-                            (size_t)n * ((size_t)(j0 + oy) + (size_t)n * (k0 + oz));
+        const int row = 4 * g + e;
+        const size_t cell = (size_t)(iseg * 16 + m) +
+                            (size_t)n * ((size_t)(j0 + row % kRY) + (size_t)n * (k0 + row / kRY));
         yout[(size_t)b * N + cell] = acc[e] * yscale;
     }
 }
@@ -347,25 +373,14 @@ __global__ void __launch_bounds__(256) k_conv4_rows(int n, int batch, const uint
                 for (int oy = 0; oy < kRY; ++oy) {
                     const int dy = iy - 1 - oy;
                     if (dy < -1 || dy > 1) continue;
-                    acc[oy][oz] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, B[(dz + 1) * 3 + dy + 1],
+                    acc[oy][oz] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(B[(dz + 1) * 3 + dy + 1], a,
                                                                             acc[oy][oz], 0, 0, 0);
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
         }
     }
-    const int nn = lane & 15;
-#pragma unroll
-    for (int oz = 0; oz < kRZ; ++oz)
-#pragma unroll
-        for (int oy = 0; oy < kRY; ++oy)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const size_t cell = (size_t)(iseg * 16 + 4 * g + e) +
-                                    (size_t)n * ((size_t)(j0 + oy) + (size_t)n * (k0 + oz));
-                const float v = acc[oy][oz][e];
-                out[((size_t)b * N + cell) * 16 + nn] = f2bf(v > 0.f ? v : 0.f);
-            }
+    store_rows(acc, out + (size_t)b * N * 16, n, iseg * 16 + m, j0, k0, g, 1);
 }
 
 // Weight gradient of one layer: partial sums over this wavefront's cells of
@@ -475,6 +490,26 @@ __global__ void k_pack_final(const float* __restrict__ w, v4s* __restrict__ wfin
     wfin[t] = v;
 }
 
+// Pack a 16 -> 16 layer for k_conv16_pairs: operand (c, s, dz) at lane
+// (n = co, g) holds in entry j the weight of channel 8 (g & 1) + j for item
+// rr = 2 s + (g >> 1) - c of the output row's run, rr = 3 (dy + 1) + dx + 1,
+// zero outside 0..8.
+__global__ void k_pack_pairs(const float* __restrict__ w, v8s* __restrict__ wpp) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * kSlots * 3 * 64) return;
+    const int op = t / 64, lane = t % 64;
+    const int dz = op % 3, s = (op / 3) % kSlots, c = op / (3 * kSlots);
+    const int co = lane & 15, g = lane >> 4, rr = 2 * s + (g >> 1) - c;
+    v8s v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        float x = 0.f;
+        if (rr >= 0 && rr < 9) x = w[((size_t)co * 16 + 8 * (g & 1) + j) * 27 + dz * 9 + rr];
+        v[j] = (short)f2bf(x);
+    }
+    wpp[t] = v;
+}
+
 // Pack one layer's FP32 weights [co][ci][27] into per-lane BF16 B operands.
 // Forward: out channel n = co, K entry (tap, ci).  Data gradient (tflip): out
 // channel n = ci, K entry (tap', co) with weight W[co][ci][26 - tap'].
@@ -559,9 +594,17 @@ size_t net_weight_offset(int layer) {
 }
 
 // Forward operands: layer 1 for k_conv (7 K-blocks), layers 2-4 (27 each),
-// layer 1 again for k_conv4_rows (9 K-blocks), then layer 4 for
-// k_conv16_final_rows (27 taps x 4 channel groups).
-size_t net_packed_bytes() { return ((size_t)(7 + 27 + 27 + 27 + 9) * 64 + 27 * 4) * sizeof(v4s); }
+// layer 1 again for k_conv4_rows (9 K-blocks), layer 4 for
+// k_conv16_final_rows (27 taps x 4 channel groups), then layers 2 and 3 for
+// k_conv16_pairs (30 K = 32 operands each).
+constexpr size_t kPackV4 = (size_t)(7 + 27 + 27 + 27 + 9) * 64 + 27 * 4;
+constexpr int kPairOps = 2 * kSlots * 3 * 64;
+static_assert(kPackV4 * sizeof(v4s) % sizeof(v8s) == 0, "pair operands stay 16-byte aligned");
+size_t net_packed_bytes() { return kPackV4 * sizeof(v4s) + (size_t)2 * kPairOps * sizeof(v8s); }
+static const v8s* pair_ops(const void* wpk, int layer) {
+    return reinterpret_cast<const v8s*>(reinterpret_cast<const v4s*>(wpk) + kPackV4) +
+           (size_t)(layer - 1) * kPairOps;
+}
 
 void net_pack_forward(hipStream_t s, const float* w32, void* wpk) {
     v4s* p = reinterpret_cast<v4s*>(wpk);
@@ -577,6 +620,9 @@ void net_pack_forward(hipStream_t s, const float* w32, void* wpk) {
                        w32 + net_weight_offset(0), 2, 16, p);
     p += 9 * 64;
     hipLaunchKernelGGL(k_pack_final, dim3(1), dim3(128), 0, s, w32 + net_weight_offset(3), p);
+    for (int l = 1; l < 3; ++l)
+        hipLaunchKernelGGL(k_pack_pairs, dim3((kPairOps + 255) / 256), dim3(256), 0, s,
+                           w32 + net_weight_offset(l), const_cast<v8s*>(pair_ops(wpk, l)));
 }
 
 static dim3 conv_grid(int n, int batch) {
@@ -595,11 +641,8 @@ void net_forward(hipStream_t s, int n, int batch, const void* wpk, const uint16_
     const v4s* p = reinterpret_cast<const v4s*>(wpk);
     const dim3 GR = conv_rows_grid(n, batch), B(256);
     hipLaunchKernelGGL(k_conv4_rows, GR, B, 0, s, n, batch, x4, p + (7 + 27 + 27 + 27) * 64, a);
-    p += 7 * 64;
-    hipLaunchKernelGGL(k_conv16_rows, GR, B, 0, s, n, batch, a, p, 1, b);
-    p += 27 * 64;
-    hipLaunchKernelGGL(k_conv16_rows, GR, B, 0, s, n, batch, b, p, 1, a);
-    p += 27 * 64;
+    hipLaunchKernelGGL(k_conv16_pairs, GR, B, 0, s, n, batch, a, pair_ops(wpk, 1), 1, b);
+    hipLaunchKernelGGL(k_conv16_pairs, GR, B, 0, s, n, batch, b, pair_ops(wpk, 2), 1, a);
     hipLaunchKernelGGL(k_conv16_final_rows, GR, B, 0, s, n, batch, a,
                        reinterpret_cast<const v4s*>(wpk) + (7 + 27 + 27 + 27 + 9) * 64, y, yscale);
 }
