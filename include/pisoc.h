@@ -471,6 +471,21 @@ pisoc_status pisoc_net_grad(int32_t n, int32_t batch, const float* d_w, const fl
                             const float* d_t, float* d_grad, double* h_loss, void* d_ws,
                             size_t ws_bytes, void* hip_stream);
 
+/* Training on what the solve measures.  For sample i with its captured
+ * pressure system (FP64 [batch][n^3] device arrays: right-hand side d_b,
+ * diagonal d_diag and w = rho/a_P in d_wk, as pisoc_fields returns them) and
+ * g = net(x_i):  u = M g, alpha = g.b / g.u (the rescale the solve applies to
+ * a guess), and the loss L_i = |b - alpha u|^2 / |b|^2, the relative residual
+ * the solve would start from; L is invariant to the scales of g and b.  The
+ * call returns the batch mean of L_i in h_loss (host, may be NULL; then it
+ * synchronises) and its gradient with respect to the weights in d_grad
+ * (PISOC_NET_NWEIGHTS FP32, overwritten).  A sample with g.u <= 0 or b = 0
+ * counts L_i = 1 with zero gradient. */
+pisoc_status pisoc_net_grad_residual(int32_t n, int32_t batch, const float* d_w, const float* d_x,
+                                     const double* d_b, const double* d_diag, const double* d_wk,
+                                     float* d_grad, double* h_loss, void* d_ws, size_t ws_bytes,
+                                     void* hip_stream);
+
 /* One Adam update of nw FP32 weights (step counts from 1).  Asynchronous. */
 pisoc_status pisoc_net_adam(int32_t nw, float* d_w, const float* d_g, float* d_m, float* d_v,
                             int32_t step, float lr, float beta1, float beta2, float eps,

@@ -122,6 +122,8 @@ def _bind_conv(L):
     L.ora_conv_forward.restype = C.c_int
     L.ora_conv_backward.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, dp, dp]
     L.ora_conv_backward.restype = C.c_int
+    L.ora_conv_backward_dy.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, dp]
+    L.ora_conv_backward_dy.restype = C.c_int
     L.ora_conv_nweights.argtypes = []
     L.ora_conv_nweights.restype = C.c_int32
 
@@ -350,6 +352,34 @@ def conv_backward(w, x, t):
     loss = C.c_double(0.0)
     lib().ora_conv_backward(n, batch, _p(w), _p(x), _p(t), _p(g), C.byref(loss))
     return loss.value, g
+
+
+def conv_backward_dy(w, x, dy):
+    """Weight gradient of sum dy * net(x) (dy: [batch][n^3] output gradient)."""
+    w = _f64(w); x = _f64(x); dy = _f64(dy)
+    batch = x.shape[0]
+    n = round((x.size // (2 * batch)) ** (1 / 3))
+    g = np.empty_like(w)
+    lib().ora_conv_backward_dy(n, batch, _p(w), _p(x), _p(dy), _p(g))
+    return g
+
+
+def residual_loss(psidt, K, b, g):
+    """The relative residual a solve started from the guess g begins with, and
+    its gradient with respect to g: u = M g, alpha = g.b / g.u (the start
+    rescale of the learned guess), r = b - alpha u, L = |r|^2 / |b|^2.
+    Differentiating alpha (d alpha = (b - 2 alpha u).dg / g.u, M symmetric):
+    dL/dg = -(2/|b|^2) [ (u.r / g.u) (b - 2 alpha u) + alpha M r ]."""
+    b = _f64(b); g = _f64(g)
+    u = helm_apply(psidt, K, g)
+    gu = float(np.sum(g * u))
+    alpha = float(np.sum(g * b)) / gu
+    r = b - alpha * u
+    bb = float(np.sum(b * b))
+    loss = float(np.sum(r * r)) / bb
+    grad = -(2.0 / bb) * (float(np.sum(u * r)) / gu * (b - 2.0 * alpha * u)
+                          + alpha * helm_apply(psidt, K, r))
+    return loss, grad
 
 
 # ---------------------------------------------------------------- whole step

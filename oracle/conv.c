@@ -171,3 +171,41 @@ int ora_conv_backward(int32_t n, int32_t batch, const double* w, const double* x
     free(gin);
     return 0;
 }
+
+/* Weight gradient of sum_b sum_P dy[b][P] y[b][P] for a given output
+ * gradient dy [batch][n^3]: back-propagation of any loss whose derivative with
+ * respect to the network output is dy (summed over the batch). */
+int ora_conv_backward_dy(int32_t n, int32_t batch, const double* w, const double* x, const double* dy,
+                         double* grad_w) {
+    size_t N = (size_t)n * n * n;
+    int nw = ora_conv_nweights();
+    memset(grad_w, 0, sizeof(double) * nw);
+    double* a1 = (double*)malloc(sizeof(double) * N * 16);
+    double* a2 = (double*)malloc(sizeof(double) * N * 16);
+    double* a3 = (double*)malloc(sizeof(double) * N * 16);
+    double* g = (double*)malloc(sizeof(double) * N * 16);
+    double* gin = (double*)malloc(sizeof(double) * N * 16);
+    for (int bi = 0; bi < batch; ++bi) {
+        const double* xb = x + (size_t)bi * N * 2;
+        layer_fwd(n, 2, 16, w + woff(0), xb, a1, 1);
+        layer_fwd(n, 16, 16, w + woff(1), a1, a2, 1);
+        layer_fwd(n, 16, 16, w + woff(2), a2, a3, 1);
+        memcpy(g, dy + (size_t)bi * N, sizeof(double) * N);
+        layer_gradw(n, 16, 1, a3, g, grad_w + woff(3));
+        layer_gradin(n, 16, 1, w + woff(3), g, gin);
+        for (size_t q = 0; q < N * 16; ++q) g[q] = a3[q] > 0.0 ? gin[q] : 0.0;
+        layer_gradw(n, 16, 16, a2, g, grad_w + woff(2));
+        layer_gradin(n, 16, 16, w + woff(2), g, gin);
+        for (size_t q = 0; q < N * 16; ++q) g[q] = a2[q] > 0.0 ? gin[q] : 0.0;
+        layer_gradw(n, 16, 16, a1, g, grad_w + woff(1));
+        layer_gradin(n, 16, 16, w + woff(1), g, gin);
+        for (size_t q = 0; q < N * 16; ++q) g[q] = a1[q] > 0.0 ? gin[q] : 0.0;
+        layer_gradw(n, 2, 16, xb, g, grad_w + woff(0));
+    }
+    free(a1);
+    free(a2);
+    free(a3);
+    free(g);
+    free(gin);
+    return 0;
+}

@@ -145,6 +145,8 @@ int32_t ora_conv_nweights(void);
 int ora_conv_forward(int32_t n, int32_t batch, const double* w, const double* x, double* y);
 int ora_conv_backward(int32_t n, int32_t batch, const double* w, const double* x, const double* t,
                       double* grad_w, double* loss);
+int ora_conv_backward_dy(int32_t n, int32_t batch, const double* w, const double* x, const double* dy,
+                         double* grad_w);
 
 #ifdef __cplusplus
 }

@@ -569,6 +569,94 @@ __global__ void __launch_bounds__(256) k_mse(const float* __restrict__ y, const 
     block_partials<1, 0u>(v, part);
 }
 
+// ---- training on the solve's own measure ----
+// For one sample with the captured system (b, diag, w) of M x = b and the
+// network output g: u = M g, alpha = g.b / g.u (the start rescale of the
+// solve), r = b - alpha u and the loss L = |r|^2 / |b|^2, the relative
+// residual the solve starts from (invariant to the scale of g and b).  With
+// c = g.u:  dL/dg = -(2 / |b|^2) [ (u.r / c) (b - 2 alpha u) + alpha M r ].
+// M v = diag v - (1/h^2) sum_f K_f v_nb(f), K_f = I4(w) on face f: the
+// pressure operator written with its diagonal.  FP64 arithmetic on the FP32
+// network output.
+constexpr int kResBlocks = 64;   // blocks per sample (grid kResBlocks x batch)
+
+template <typename V>
+__device__ inline double m_offdiag(const double* __restrict__ w, const CellIdx& c, V&& v) {
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s += i4(w, c, d, 0) * v(c.sh(d, 1)) + i4(w, c, d, -1) * v(c.sh(d, -1));
+    return s;
+}
+
+__global__ void __launch_bounds__(256) k_res_u(int n, double inv_h2, const double* __restrict__ b,
+                                               const double* __restrict__ diag,
+                                               const double* __restrict__ w, const float* __restrict__ y,
+                                               double* __restrict__ u, double* part) {
+    const BlockXYZ bx = block_xyz();
+    const size_t N = (size_t)n * n * n, base = (size_t)bx.y * N;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // g.b, g.u, u.b, u.u, b.b
+    for (size_t i = (size_t)bx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
+        const CellIdx c(n, (int)(i % n), (int)((i / n) % n), (int)(i / ((size_t)n * n)), base);
+        const size_t P = c.self();
+        const double gP = y[P], bP = b[P];
+        const double uP = diag[P] * gP - inv_h2 * m_offdiag(w, c, [&](size_t Q) { return (double)y[Q]; });
+        u[P] = uP;
+        v[0] += gP * bP;
+        v[1] += gP * uP;
+        v[2] += uP * bP;
+        v[3] += uP * uP;
+        v[4] += bP * bP;
+    }
+    block_partials<5, 0u>(v, part);
+}
+
+// Per sample: coef = (alpha, u.r / c, -2 / (|b|^2 batch)) and its loss; one
+// block walks the samples in order and writes the batch mean to loss.
+__global__ void __launch_bounds__(256) k_res_coef(int batch, const double* __restrict__ part,
+                                                  double* __restrict__ coef, double* loss) {
+    double total = 0.0;
+    for (int sm = 0; sm < batch; ++sm) {
+        double t[5];
+        reduce_partials_strided<5, 0u>(part, (size_t)kResBlocks * batch, (size_t)sm * kResBlocks,
+                                       kResBlocks, t);
+        if (threadIdx.x == 0) {
+            const double gb = t[0], gu = t[1], ub = t[2], uu = t[3], bb = t[4];
+            const bool ok = gu > 0.0 && bb > 0.0;
+            const double alpha = ok ? gb / gu : 0.0;
+            const double ur = ub - alpha * uu;
+            coef[3 * sm + 0] = alpha;
+            coef[3 * sm + 1] = ok ? ur / gu : 0.0;
+            coef[3 * sm + 2] = ok ? -2.0 / (bb * batch) : 0.0;
+            total += ok ? (bb - 2.0 * alpha * ub + alpha * alpha * uu) / bb : 1.0;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = total / batch;
+}
+
+// Output gradient dL/dg as BF16 [cell][4] (channel 0), for the backward pass.
+__global__ void __launch_bounds__(256) k_res_dy(int n, double inv_h2, const double* __restrict__ b,
+                                                const double* __restrict__ diag,
+                                                const double* __restrict__ w,
+                                                const double* __restrict__ u,
+                                                const double* __restrict__ coef,
+                                                uint16_t* __restrict__ dy) {
+    const BlockXYZ bx = block_xyz();
+    const size_t N = (size_t)n * n * n, base = (size_t)bx.y * N;
+    const double alpha = coef[3 * bx.y], beta = coef[3 * bx.y + 1], sc = coef[3 * bx.y + 2];
+    for (size_t i = (size_t)bx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
+        const CellIdx c(n, (int)(i % n), (int)((i / n) % n), (int)(i / ((size_t)n * n)), base);
+        const size_t P = c.self();
+        auto r = [&](size_t Q) { return b[Q] - alpha * u[Q]; };
+        const double Mr = diag[P] * r(P) - inv_h2 * m_offdiag(w, c, r);
+        const double g = sc * (beta * (b[P] - 2.0 * alpha * u[P]) + alpha * Mr);
+        dy[4 * P + 0] = f2bf((float)g);
+        dy[4 * P + 1] = 0;
+        dy[4 * P + 2] = 0;
+        dy[4 * P + 3] = 0;
+    }
+}
+
 __global__ void k_adam(int nw, float* __restrict__ w, const float* __restrict__ g,
                        float* __restrict__ m, float* __restrict__ v, float lr, float b1, float b2,
                        float eps, float c1, float c2) {
@@ -649,7 +737,7 @@ void net_forward(hipStream_t s, int n, int batch, const void* wpk, const uint16_
 
 // ---- training workspace ----
 struct NetWs {
-    size_t x4, a1, a2, a3, y, g1, g2, dy, wf, wb, part, lpart, total;
+    size_t x4, a1, a2, a3, y, g1, g2, dy, wf, wb, part, lpart, ru, rpart, rcoef, total;
     int nwaves, spw;
     unsigned lblocks;
 };
@@ -679,6 +767,9 @@ static NetWs net_layout(int n, int batch) {
     L.wb = take((size_t)3 * 27 * 64 * sizeof(v4s));
     L.part = take((size_t)L.nwaves * 27 * 256 * sizeof(float));
     L.lpart = take((size_t)L.lblocks * sizeof(double) + sizeof(double));
+    L.ru = take(cells * sizeof(double));
+    L.rpart = take((size_t)5 * kResBlocks * batch * sizeof(double));
+    L.rcoef = take((size_t)3 * batch * sizeof(double));
     L.total = off;
     return L;
 }
@@ -716,15 +807,10 @@ pisoc_status pisoc_net_forward(int32_t n, int32_t batch, const float* d_w, const
     return hipGetLastError() == hipSuccess ? PISOC_OK : PISOC_ERR_HIP;
 }
 
-pisoc_status pisoc_net_grad(int32_t n, int32_t batch, const float* d_w, const float* d_x,
-                            const float* d_t, float* d_grad, double* h_loss, void* d_ws,
-                            size_t ws_bytes, void* stream) {
-    if (!net_shape_ok(n, batch) || !d_w || !d_x || !d_t || !d_grad) return PISOC_ERR_INVALID;
-    NetWs L = net_layout(n, batch);
-    if (!d_ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(d_ws) % 256) != 0)
-        return PISOC_ERR_WORKSPACE;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    char* ws = reinterpret_cast<char*>(d_ws);
+// Forward pass of a training step keeping every activation in the
+// workspace (y at L.y), after packing the forward and data-gradient weights.
+static void grad_forward(hipStream_t s, const NetWs& L, char* ws, int n, int batch, const float* d_w,
+                         const float* d_x) {
     auto U = [&](size_t off) { return reinterpret_cast<uint16_t*>(ws + off); };
     const size_t cells = (size_t)batch * n * n * n;
     const dim3 G = conv_grid(n, batch), B(256);
@@ -741,7 +827,6 @@ pisoc_status pisoc_net_grad(int32_t n, int32_t batch, const float* d_w, const fl
             hipLaunchKernelGGL(k_pack<16>, dim3((27 * 64 + 255) / 256), B, 0, s,
                                d_w + net_weight_offset(l), 16, 16, 1, wb + (l - 1) * 27 * 64);
     }
-    // forward keeping every activation
     const v4s* wf = reinterpret_cast<const v4s*>(ws + L.wf);
     float* y = reinterpret_cast<float*>(ws + L.y);
     hipLaunchKernelGGL((k_conv<4, false>), G, B, 0, s, n, batch, U(L.x4), wf, (const uint16_t*)nullptr,
@@ -752,13 +837,14 @@ pisoc_status pisoc_net_grad(int32_t n, int32_t batch, const float* d_w, const fl
                        (const uint16_t*)nullptr, 1, U(L.a3), (float*)nullptr, 1.f);
     hipLaunchKernelGGL((k_conv<16, true>), G, B, 0, s, n, batch, U(L.a3), wf + 61 * 64,
                        (const uint16_t*)nullptr, 0, (uint16_t*)nullptr, y, 1.f);
-    // loss and output gradient
-    double* lpart = reinterpret_cast<double*>(ws + L.lpart);
-    hipLaunchKernelGGL(k_mse, dim3(L.lblocks), B, 0, s, y, d_t, cells, (float)(2.0 / (double)cells),
-                       U(L.dy), lpart);
-    double* loss_dev = lpart + L.lblocks;
-    sum_partials(s, lpart, L.lblocks, loss_dev);
-    // backward: layer 4 (linear), 3, 2, 1
+}
+
+// Weight gradient from the output gradient dy (BF16 [cell][4] at L.dy) and
+// the activations grad_forward kept.
+static void grad_backward(hipStream_t s, const NetWs& L, char* ws, int n, int batch, float* d_grad) {
+    auto U = [&](size_t off) { return reinterpret_cast<uint16_t*>(ws + off); };
+    const dim3 G = conv_grid(n, batch), B(256);
+    const v4s* wb = reinterpret_cast<const v4s*>(ws + L.wb);
     float* part = reinterpret_cast<float*>(ws + L.part);
     const dim3 GW((L.nwaves + 3) / 4);
     auto wgrad16 = [&](const uint16_t* in, const uint16_t* gr, int gp, int cout, int layer) {
@@ -767,6 +853,7 @@ pisoc_status pisoc_net_grad(int32_t n, int32_t batch, const float* d_w, const fl
         hipLaunchKernelGGL(k_wgrad_reduce<16>, dim3((27 * 256 + 255) / 256), B, 0, s, part, L.nwaves,
                            16, cout, d_grad + net_weight_offset(layer));
     };
+    // layer 4 (linear), 3, 2, 1
     wgrad16(U(L.a3), U(L.dy), 4, 1, 3);
     hipLaunchKernelGGL((k_conv<4, false>), G, B, 0, s, n, batch, U(L.dy), wb + 2 * 27 * 64, U(L.a3),
                        0, U(L.g1), (float*)nullptr, 1.f);
@@ -780,15 +867,67 @@ pisoc_status pisoc_net_grad(int32_t n, int32_t batch, const float* d_w, const fl
                        L.nwaves);
     hipLaunchKernelGGL(k_wgrad_reduce<4>, dim3((7 * 256 + 255) / 256), B, 0, s, part, L.nwaves, 2, 16,
                        d_grad + net_weight_offset(0));
+}
+
+static pisoc_status read_loss(hipStream_t s, const double* loss_dev, double scale, double* h_loss) {
     if (hipGetLastError() != hipSuccess) return PISOC_ERR_HIP;
     if (h_loss) {
         double l = 0.0;
         if (hipMemcpyAsync(&l, loss_dev, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return PISOC_ERR_HIP;
-        *h_loss = l / (double)cells;
+        *h_loss = l * scale;
     }
     return PISOC_OK;
+}
+
+pisoc_status pisoc_net_grad(int32_t n, int32_t batch, const float* d_w, const float* d_x,
+                            const float* d_t, float* d_grad, double* h_loss, void* d_ws,
+                            size_t ws_bytes, void* stream) {
+    if (!net_shape_ok(n, batch) || !d_w || !d_x || !d_t || !d_grad) return PISOC_ERR_INVALID;
+    NetWs L = net_layout(n, batch);
+    if (!d_ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(d_ws) % 256) != 0)
+        return PISOC_ERR_WORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* ws = reinterpret_cast<char*>(d_ws);
+    const size_t cells = (size_t)batch * n * n * n;
+    grad_forward(s, L, ws, n, batch, d_w, d_x);
+    // loss and output gradient
+    double* lpart = reinterpret_cast<double*>(ws + L.lpart);
+    hipLaunchKernelGGL(k_mse, dim3(L.lblocks), dim3(256), 0, s, reinterpret_cast<const float*>(ws + L.y),
+                       d_t, cells, (float)(2.0 / (double)cells),
+                       reinterpret_cast<uint16_t*>(ws + L.dy), lpart);
+    double* loss_dev = lpart + L.lblocks;
+    sum_partials(s, lpart, L.lblocks, loss_dev);
+    grad_backward(s, L, ws, n, batch, d_grad);
+    return read_loss(s, loss_dev, 1.0 / (double)cells, h_loss);
+}
+
+pisoc_status pisoc_net_grad_residual(int32_t n, int32_t batch, const float* d_w, const float* d_x,
+                                     const double* d_b, const double* d_diag, const double* d_wk,
+                                     float* d_grad, double* h_loss, void* d_ws, size_t ws_bytes,
+                                     void* stream) {
+    if (!net_shape_ok(n, batch) || !d_w || !d_x || !d_b || !d_diag || !d_wk || !d_grad)
+        return PISOC_ERR_INVALID;
+    NetWs L = net_layout(n, batch);
+    if (!d_ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(d_ws) % 256) != 0)
+        return PISOC_ERR_WORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* ws = reinterpret_cast<char*>(d_ws);
+    grad_forward(s, L, ws, n, batch, d_w, d_x);
+    const double h = 2.0 * M_PI / n, inv_h2 = 1.0 / (h * h);
+    double* u = reinterpret_cast<double*>(ws + L.ru);
+    double* rpart = reinterpret_cast<double*>(ws + L.rpart);
+    double* coef = reinterpret_cast<double*>(ws + L.rcoef);
+    double* loss_dev = reinterpret_cast<double*>(ws + L.lpart);
+    const dim3 GR(kResBlocks, batch), B(256);
+    hipLaunchKernelGGL(k_res_u, GR, B, 0, s, n, inv_h2, d_b, d_diag, d_wk,
+                       reinterpret_cast<const float*>(ws + L.y), u, rpart);
+    hipLaunchKernelGGL(k_res_coef, dim3(1), B, 0, s, batch, rpart, coef, loss_dev);
+    hipLaunchKernelGGL(k_res_dy, GR, B, 0, s, n, inv_h2, d_b, d_diag, d_wk, u, coef,
+                       reinterpret_cast<uint16_t*>(ws + L.dy));
+    grad_backward(s, L, ws, n, batch, d_grad);
+    return read_loss(s, loss_dev, 1.0, h_loss);
 }
 
 pisoc_status pisoc_net_adam(int32_t nw, float* d_w, const float* d_g, float* d_m, float* d_v,

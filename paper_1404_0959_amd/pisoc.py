@@ -35,6 +35,7 @@ EXPORTED = [
     "pisoc_helm_solve_noalloc",
     "pisoc_profile", "pisoc_profile_read",
     "pisoc_net_workspace_bytes", "pisoc_net_forward", "pisoc_net_grad", "pisoc_net_adam",
+    "pisoc_net_grad_residual",
     "pisoc_net_inputs",
     "pisoc_ens_workspace_bytes", "pisoc_ens_init", "pisoc_ens_step", "pisoc_ens_fields",
     "pisoc_ens_get_stats", "pisoc_ens_time", "pisoc_ens_steps_done", "pisoc_ens_num_classes",
@@ -150,6 +151,9 @@ def lib():
     L.pisoc_net_forward.restype = C.c_int
     L.pisoc_net_grad.argtypes = [i32, i32, fp, fp, fp, fp, C.POINTER(f64), vp, sz, vp]
     L.pisoc_net_grad.restype = C.c_int
+    L.pisoc_net_grad_residual.argtypes = [i32, i32, fp, fp, vp, vp, vp, fp, C.POINTER(f64), vp, sz,
+                                          vp]
+    L.pisoc_net_grad_residual.restype = C.c_int
     L.pisoc_net_adam.argtypes = [i32, fp, fp, fp, fp, i32, C.c_float, C.c_float, C.c_float,
                                  C.c_float, vp]
     L.pisoc_net_adam.restype = C.c_int
@@ -520,6 +524,20 @@ class Net:
                                   _stream_ptr(torch, self.stream))
         if st != OK:
             raise PisocError(st, "pisoc_net_grad")
+        return loss.value, g
+
+    def grad_residual(self, w, x, b, diag, wk, out=None):
+        """(loss, FP32 gradient) of the relative residual |b - alpha M g|^2/|b|^2
+        the solve would start from (b, diag, wk: FP64 [batch, n^3] systems)."""
+        torch = self.torch
+        g = out if out is not None else torch.empty_like(w)
+        loss = C.c_double(0.0)
+        st = lib().pisoc_net_grad_residual(self.n, x.shape[0], w.data_ptr(), x.data_ptr(),
+                                           b.data_ptr(), diag.data_ptr(), wk.data_ptr(),
+                                           g.data_ptr(), C.byref(loss), self.ws.data_ptr(),
+                                           self.nbytes, _stream_ptr(torch, self.stream))
+        if st != OK:
+            raise PisocError(st, "pisoc_net_grad_residual")
         return loss.value, g
 
     def adam(self, w, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

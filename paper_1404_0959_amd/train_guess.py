@@ -1,6 +1,10 @@
 """Train the learned pressure guess and measure what it gains.
 
-    python -m paper_1404_0959_amd.train_guess [--epochs 30] [--out weights/guess.npy]
+    python -m paper_1404_0959_amd.train_guess [--epochs 20] [--out weights/guess.npy]
+        [--loss residual|mse] [--init weights/guess_hit32.npy]
+
+(the committed weights/guess_hit32_residual.npy: the defaults; the earlier
+weights/guess_hit32.npy: --loss mse --epochs 30 --out weights/guess_hit32.npy)
 
 Data: 20 seeded 32^3 decaying-HIT runs (Mach 0.2, Stokes 0.1, pressure
 tolerance 1e-8), 100 steps each, first-corrector systems -> 2000 snapshots.
@@ -23,14 +27,18 @@ from . import learn
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seeds", type=int, default=20)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "weights",
-                                                  "guess_hit32.npy"))
+                                                  "guess_hit32_residual.npy"))
     ap.add_argument("--eval-sizes", default="32,128,256")
+    ap.add_argument("--loss", default="residual", choices=["mse", "residual"],
+                    help="mse: against the solution p'/s1; residual: the relative residual "
+                         "|b - alpha M g|^2/|b|^2 the solve would start from")
+    ap.add_argument("--init", default=None, help="start from these weights (.npy)")
     ap.add_argument("--report", default=None)
     ap.add_argument("--extra", default="",
                     help="extra training data at other sizes, e.g. 64:4:25,128:2:12 "
@@ -42,24 +50,31 @@ def main():
     import torch
     from . import pisoc as P
     t0 = time.time()
-    x, t = learn.generate(range(args.seeds), args.steps, n=32, log=log)
-    xs, ts = [x], [t]
-    nsnap = x.shape[0]
+    res = args.loss == "residual"
+    xs, ts, sys_ = [], [], []
+    sets = [(32, range(args.seeds), args.steps)]
     for spec in [e for e in args.extra.split(",") if e]:
         n_e, s_e, st_e = (int(v) for v in spec.split(":"))
-        xe, te = learn.generate(range(100, 100 + s_e), st_e, n=n_e, log=log)
-        xs.append(xe)
-        ts.append(te)
-        nsnap += xe.shape[0]
+        sets.append((n_e, range(100, 100 + s_e), st_e))
+    for n_e, seeds, steps in sets:
+        out = learn.generate(seeds, steps, n=n_e, log=log, systems=res)
+        xs.append(out[0])
+        ts.append(out[1])
+        if res:
+            sys_.append(out[2])
+    nsnap = sum(x.shape[0] for x in xs)
     log(f"{nsnap} snapshots in {time.time() - t0:.1f}s")
     t1 = time.time()
-    w, hist = learn.train(xs, ts, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
+    w0 = np.load(args.init, allow_pickle=False) if args.init else None
+    w, hist = learn.train(xs, ts, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log,
+                          w0=w0, systems=sys_ if res else None)
     log(f"trained in {time.time() - t1:.1f}s, loss {hist[0]:.4e} -> {hist[-1]:.4e}")
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     np.save(args.out, w.cpu().numpy())
-    del x, t, xs, ts
+    del xs, ts, sys_
     torch.cuda.empty_cache()
-    report = dict(snapshots=nsnap, extra=args.extra, epochs=args.epochs, loss_history=hist,
+    report = dict(snapshots=nsnap, extra=args.extra, epochs=args.epochs, loss=args.loss,
+                  init=args.init, loss_history=hist,
                   weights=os.path.basename(args.out), eval={})
     for n in [int(v) for v in args.eval_sizes.split(",")]:
         seeds = (20, 21, 22, 23, 24) if n <= 32 else ((20,) if n >= 256 else (20, 21))

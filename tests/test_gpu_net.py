@@ -96,6 +96,45 @@ def test_gradient_matches_oracle(P, ora):
         assert cos >= 0.999, (l, cos)
 
 
+def test_residual_gradient_matches_oracle(P, ora):
+    """Training on the relative residual the solve starts from: loss and weight
+    gradient of pisoc_net_grad_residual on two captured 16^3 pressure systems
+    against the oracle's residual loss, back-propagated by the oracle network
+    (same BF16 weights and inputs).  The loss and the output gradient are
+    taken at the GPU network's own output (the loss is small, so the forward
+    pass's BF16 error would dominate a comparison with the FP64 network): loss
+    to 1e-3 relative; weight gradient of every layer with cosine >= 0.999."""
+    from paper_1404_0959_amd.inputs import make_hit_case
+    from paper_1404_0959_amd.learn import load_weights
+    n, batch = 16, 2
+    w = bf16(load_weights().cpu().numpy())
+    sys_ = []
+    for seed in (3, 4):
+        o = ora.Oracle.from_case(make_hit_case(n, seed, mach=0.2, stokes=(0.1,)), p_tol=1e-10,
+                                 capture=True)
+        o.step(2)
+        sys_.append({k: o.get(getattr(ora, "SYS_" + k)) for k in ("B", "DIAG", "W", "PSIDT", "K",
+                                                                   "P0")})
+    x = np.stack([bf16(ora.net_inputs(s["B"], s["DIAG"], s["P0"])[0]) for s in sys_])
+    net = P.Net(n, batch)
+    y = net.forward(dev(w), dev(x)).cpu().numpy().astype(np.float64).reshape(batch, n, n, n)
+    losses, dy = [], []
+    for i, s in enumerate(sys_):
+        L, g = ora.residual_loss(s["PSIDT"], s["K"], s["B"], y[i])
+        losses.append(L)
+        dy.append(g / batch)
+    g_cpu = ora.conv_backward_dy(w.astype(np.float64), x.astype(np.float64), np.stack(dy))
+    stack = {k: dev(np.stack([s[k].ravel() for s in sys_])) for k in ("B", "DIAG", "W")}
+    loss, g = net.grad_residual(dev(w), dev(x), stack["B"], stack["DIAG"], stack["W"])
+    g = g.cpu().numpy()
+    print(f"residual loss GPU {loss:.6e}, oracle {np.mean(losses):.6e} (per system {losses})")
+    assert abs(loss / np.mean(losses) - 1) <= 1e-3, (loss, losses)
+    for l, sl in enumerate(slices(ora)):
+        a, b = g[sl].astype(np.float64), g_cpu[sl]
+        cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+        assert cos >= 0.999, (l, cos)
+
+
 def test_adam_step(P):
     """One Adam step from zero moments moves every weight by lr * sign(g)."""
     import torch

@@ -92,3 +92,27 @@ def test_gradient_matches_central_differences(ora):
         wm[i] -= h
         fd = (L(wp) - L(wm)) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(abs(fd), 1e-3 * np.max(np.abs(g))), (i, fd, g[i])
+
+
+def test_backward_from_output_gradient(ora):
+    """Back-propagation of a given output gradient dy: with dy = 2 (y - t) /
+    (batch n^3) it is the mean-squared-error gradient of the separate MSE pass;
+    along random weight directions v it is the central difference of
+    sum dy * net(x)."""
+    rng = np.random.default_rng(4)
+    n, batch = 4, 2
+    w = rng.standard_normal(ora.conv_nweights()) * 0.3
+    x = rng.standard_normal((batch, n, n, n, 2))
+    t = rng.standard_normal((batch, n, n, n))
+    y = ora.conv_forward(w, x)
+    _, g_mse = ora.conv_backward(w, x, t)
+    g = ora.conv_backward_dy(w, x, 2 * (y - t) / (batch * n ** 3))
+    assert np.max(np.abs(g - g_mse)) <= 1e-12 * np.max(np.abs(g_mse))
+    dy = rng.standard_normal((batch, n, n, n))
+    g = ora.conv_backward_dy(w, x, dy)
+    h = 1e-6
+    for _ in range(4):
+        v = rng.standard_normal(w.shape)
+        fd = (np.sum(dy * ora.conv_forward(w + h * v, x)) -
+              np.sum(dy * ora.conv_forward(w - h * v, x))) / (2 * h)
+        assert abs(fd - g @ v) <= 1e-6 * abs(fd), (fd, g @ v)

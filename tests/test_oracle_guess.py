@@ -125,3 +125,31 @@ def test_fallbacks(ora, sys8):
     assert alpha > 0 and fell and ratio > 1.0 and np.all(x0 == 0.0)
     dense_ratio = np.linalg.norm(b.ravel() - alpha * Mg) / np.linalg.norm(b)
     assert abs(ratio - dense_ratio) <= 1e-12
+
+
+# ------------------------------------------------- the solve's own loss
+def test_residual_loss_pins(ora, sys8):
+    """L(g) = |b - alpha M g|^2 / |b|^2 with alpha = g.b / g.(M g), and its
+    gradient: zero at the exact solution; invariant to the scale of g (the
+    gradient then scales by 1/c); for a constant g under a uniform psi/dt
+    (M 1 = psi/dt 1) the closed form 1 - (sum b)^2 / (N sum b^2); the gradient
+    equals central differences along random directions."""
+    b, psidt, K, xs = sys8["b"], sys8["psidt"], sys8["K"], sys8["xstar"]
+    L, gr = ora.residual_loss(psidt, K, b, xs)
+    assert L <= 1e-24, L
+    rng = np.random.default_rng(9)
+    g = xs + 0.3 * np.std(xs) * rng.standard_normal(xs.shape)
+    L1, g1 = ora.residual_loss(psidt, K, b, g)
+    L2, g2 = ora.residual_loss(psidt, K, b, 3.7 * g)
+    assert 0.0 < L1 and abs(L2 - L1) <= 1e-13 * L1
+    assert np.max(np.abs(3.7 * g2 - g1)) <= 1e-12 * np.max(np.abs(g1))
+    flat = np.full_like(psidt, 2.5)
+    Lc, _ = ora.residual_loss(flat, K, b, np.ones_like(b))
+    want = 1.0 - b.sum() ** 2 / (b.size * np.sum(b * b))
+    assert abs(Lc - want) <= 1e-13, (Lc, want)
+    h = 1e-6 * np.std(g)
+    for _ in range(4):
+        v = rng.standard_normal(g.shape)
+        fd = (ora.residual_loss(psidt, K, b, g + h * v)[0] -
+              ora.residual_loss(psidt, K, b, g - h * v)[0]) / (2 * h)
+        assert abs(fd - np.sum(g1 * v)) <= 1e-6 * abs(fd), (fd, np.sum(g1 * v))
