@@ -106,6 +106,12 @@ def lib():
         L.ora_helm_apply.argtypes = [C.c_int32, dp, dp, dp, dp, dp, dp]
         L.ora_pcg.argtypes = [C.c_int32, dp, dp, dp, dp, dp, dp, C.c_double, C.c_int32, dp]
         L.ora_pcg.restype = C.c_int32
+        L.ora_pcg_cheb.argtypes = [C.c_int32, dp, dp, dp, dp, dp, dp, C.c_double, C.c_int32, dp]
+        L.ora_pcg_cheb.restype = C.c_int32
+        L.ora_cheb_coef.argtypes = [C.c_int32, dp, dp, dp, dp, dp]
+        L.ora_cheb_coef.restype = None
+        L.ora_cheb_apply.argtypes = [C.c_int32, dp, dp, dp, dp, dp, dp]
+        L.ora_cheb_apply.restype = None
         if hasattr(L, "ora_conv_forward"):
             _bind_conv(L)
         L.ora_net_inputs.argtypes = [C.c_int32, dp, dp, dp, dp, dp]
@@ -191,6 +197,34 @@ def pcg(psidt, K, b, x0=None, tol=1e-10, maxit=1000):
     it = lib().ora_pcg(b.shape[0], _p(psidt), _p(K[0]), _p(K[1]), _p(K[2]), _p(b), _p(x),
                        tol, maxit, C.byref(rel))
     return x, int(it), rel.value
+
+
+def pcg_cheb(psidt, K, b, x0=None, tol=1e-10, maxit=1000):
+    """CG preconditioned by the degree-1 Chebyshev polynomial of the
+    Jacobi-scaled operator; returns (x, iterations, relres) as pcg."""
+    psidt = _f64(psidt); K = [_f64(k) for k in K]; b = _f64(b)
+    x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
+    rel = C.c_double(0.0)
+    it = lib().ora_pcg_cheb(b.shape[0], _p(psidt), _p(K[0]), _p(K[1]), _p(K[2]), _p(b), _p(x),
+                            tol, maxit, C.byref(rel))
+    return x, int(it), rel.value
+
+
+def cheb_coef(psidt, K):
+    """(c0, c1, a) of the Chebyshev preconditioner p(lambda) = c0 + c1 lambda on
+    [a, 2 - a]."""
+    psidt = _f64(psidt); K = [_f64(k) for k in K]
+    c = np.empty(3)
+    lib().ora_cheb_coef(psidt.shape[0], _p(psidt), _p(K[0]), _p(K[1]), _p(K[2]), _p(c))
+    return float(c[0]), float(c[1]), float(c[2])
+
+
+def cheb_apply(psidt, K, r):
+    """z = p(D^-1 M) D^-1 r."""
+    psidt = _f64(psidt); K = [_f64(k) for k in K]; r = _f64(r)
+    z = np.empty_like(r)
+    lib().ora_cheb_apply(r.shape[0], _p(psidt), _p(K[0]), _p(K[1]), _p(K[2]), _p(r), _p(z))
+    return z
 
 
 # ---------------------------------------------------------------- learned guess

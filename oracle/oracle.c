@@ -304,6 +304,117 @@ int32_t ora_pcg(int32_t n, const double* psidt, const double* k0, const double* 
     return converged ? it : -maxit - 1;
 }
 
+/* Degree-1 Chebyshev polynomial preconditioner, a non-learned rival of the
+ * learned guess (not in the paper).  With D = diag(M) the spectrum of D^-1 M
+ * lies in [a, b], a = min_P psidt_P / diag_P, b = 2 - a (Gershgorin: the
+ * off-diagonal entries of a row of D^-1 M sum in magnitude to
+ * 1 - psidt/diag).  z = p(D^-1 M) D^-1 r with the degree-1 p whose residual
+ * polynomial 1 - lambda p(lambda) is the degree-2 Chebyshev polynomial of
+ * [a, b] normalised to 1 at lambda = 0:
+ *   1 - lambda p(lambda) = T2((b + a - 2 lambda)/(b - a)) / T2(mu),
+ *   T2(s) = 2 s^2 - 1, mu = (b + a)/(b - a),
+ * i.e. p(lambda) = c0 + c1 lambda, c0 = 8 mu / ((b - a) T2(mu)),
+ * c1 = -8 / ((b - a)^2 T2(mu)).  p(b) = 8 a / ((b - a)^2 T2(mu)) > 0, so p is
+ * positive on [a, b] and the preconditioner symmetric positive definite.
+ * c receives c0, c1 and a. */
+void ora_cheb_coef(int32_t n, const double* psidt, const double* k0, const double* k1,
+                   const double* k2, double* c) {
+    size_t N = ncell(n);
+    const double* K[3] = {k0, k1, k2};
+    double* diag = alloc_field(N);
+    helm_diag(n, psidt, K, diag);
+    double a = 1.0;
+    for (size_t P = 0; P < N; ++P) {
+        double t = psidt[P] / diag[P];
+        if (t < a) a = t;
+    }
+    double b = 2.0 - a, mu = (b + a) / (b - a), t2 = 2.0 * mu * mu - 1.0;
+    c[0] = 8.0 * mu / ((b - a) * t2);
+    c[1] = -8.0 / ((b - a) * (b - a) * t2);
+    c[2] = a;
+    free(diag);
+}
+
+/* z = c0 D^-1 r + c1 D^-1 M D^-1 r (scratch: diag and t, N values each). */
+static void cheb_apply(int32_t n, const double* psidt, const double* const K[3], const double* c,
+                       const double* diag, const double* r, double* t, double* z) {
+    size_t N = ncell(n);
+    for (size_t P = 0; P < N; ++P) t[P] = r[P] / diag[P];
+    ora_helm_apply(n, psidt, K[0], K[1], K[2], t, z);
+    for (size_t P = 0; P < N; ++P) z[P] = c[0] * t[P] + c[1] * z[P] / diag[P];
+}
+
+void ora_cheb_apply(int32_t n, const double* psidt, const double* k0, const double* k1,
+                    const double* k2, const double* r, double* z) {
+    size_t N = ncell(n);
+    const double* K[3] = {k0, k1, k2};
+    double c[3];
+    ora_cheb_coef(n, psidt, k0, k1, k2, c);
+    double* diag = alloc_field(N);
+    double* t = alloc_field(N);
+    helm_diag(n, psidt, K, diag);
+    cheb_apply(n, psidt, K, c, diag, r, t, z);
+    free(diag);
+    free(t);
+}
+
+/* Conjugate gradients on M x = b preconditioned by the Chebyshev polynomial
+ * above; otherwise as ora_pcg (start, stopping rule, return value). */
+int32_t ora_pcg_cheb(int32_t n, const double* psidt, const double* k0, const double* k1,
+                     const double* k2, const double* b, double* x, double tol, int32_t maxit,
+                     double* relres) {
+    size_t N = ncell(n);
+    const double* K[3] = {k0, k1, k2};
+    double c[3];
+    ora_cheb_coef(n, psidt, k0, k1, k2, c);
+    double* diag = alloc_field(N);
+    double* r = alloc_field(N);
+    double* z = alloc_field(N);
+    double* p = alloc_field(N);
+    double* q = alloc_field(N);
+    double* t = alloc_field(N);
+    helm_diag(n, psidt, K, diag);
+    ora_helm_apply(n, psidt, k0, k1, k2, x, q);
+    for (size_t P = 0; P < N; ++P) r[P] = b[P] - q[P];
+    double bb = dot_field(n, b, b);
+    double rr = dot_field(n, r, r);
+    double lim = tol * tol * bb;
+    int32_t it = 0;
+    int converged = rr <= lim;
+    if (!converged) {
+        cheb_apply(n, psidt, K, c, diag, r, t, z);
+        for (size_t P = 0; P < N; ++P) p[P] = z[P];
+        double rz = dot_field(n, r, z);
+        while (it < maxit) {
+            ora_helm_apply(n, psidt, k0, k1, k2, p, q);
+            double alpha = rz / dot_field(n, p, q);
+            for (size_t P = 0; P < N; ++P) {
+                x[P] += alpha * p[P];
+                r[P] -= alpha * q[P];
+            }
+            ++it;
+            rr = dot_field(n, r, r);
+            if (rr <= lim) {
+                converged = 1;
+                break;
+            }
+            cheb_apply(n, psidt, K, c, diag, r, t, z);
+            double rz_new = dot_field(n, r, z);
+            double beta = rz_new / rz;
+            rz = rz_new;
+            for (size_t P = 0; P < N; ++P) p[P] = z[P] + beta * p[P];
+        }
+    }
+    if (relres) *relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    free(diag);
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    free(t);
+    return converged ? it : -maxit - 1;
+}
+
 /* ------------------------------------------------------------------------- */
 /* state                                                                     */
 /* ------------------------------------------------------------------------- */

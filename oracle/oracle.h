@@ -132,6 +132,13 @@ void ora_helm_apply(int32_t n, const double* psidt, const double* k0, const doub
 int32_t ora_pcg(int32_t n, const double* psidt, const double* k0, const double* k1,
                 const double* k2, const double* b, double* x, double tol, int32_t maxit,
                 double* relres);
+void ora_cheb_coef(int32_t n, const double* psidt, const double* k0, const double* k1,
+                   const double* k2, double* c);
+void ora_cheb_apply(int32_t n, const double* psidt, const double* k0, const double* k1,
+                    const double* k2, const double* r, double* z);
+int32_t ora_pcg_cheb(int32_t n, const double* psidt, const double* k0, const double* k1,
+                     const double* k2, const double* b, double* x, double tol, int32_t maxit,
+                     double* relres);
 
 /* ---- learned pressure guess: inputs and solve start (guess.c) ---- */
 int ora_net_inputs(int32_t n, const double* b, const double* diag, const double* p0, double* x,

@@ -107,3 +107,63 @@ def test_pcg_stopping_rule(ora, hit_system):
     # monotone: a tighter tolerance never needs fewer iterations
     its = [ora.pcg(s["psidt"], s["K"], s["b"], tol=t)[1] for t in (1e-4, 1e-6, 1e-8, 1e-10)]
     assert its == sorted(its) and its[0] >= 1
+
+
+# ------------------------------------- Chebyshev polynomial preconditioner
+def test_cheb_polynomial_is_the_minimax_one(ora, hit_system):
+    """The residual polynomial 1 - lambda p(lambda) of the degree-1
+    preconditioner equioscillates on [a, 2 - a] (+e at both ends, -e at the
+    midpoint, e = its maximum modulus), which fixes the degree-2 minimax
+    polynomial normalised at 0; a is min psi/dt / diag, and the dense spectrum
+    of D^-1 M lies inside [a, 2 - a]."""
+    s = hit_system
+    c0, c1, a = ora.cheb_coef(s["psidt"], s["K"])
+    assert a == np.min(s["psidt"] / s["diag"])
+    b = 2.0 - a
+    res = lambda lam: 1.0 - lam * (c0 + c1 * lam)
+    e = res(a)
+    assert 0 < e < 1 and abs(res(b) - e) <= 1e-14 and abs(res((a + b) / 2) + e) <= 1e-14
+    lam = np.linspace(a, b, 1001)
+    assert np.max(np.abs(res(lam))) <= e * (1 + 1e-12)
+    M = assemble(ora, s["psidt"], s["K"], s["n"])
+    d = s["diag"].ravel()
+    ev = np.linalg.eigvalsh(M / np.sqrt(np.outer(d, d)))
+    assert a - 1e-12 <= ev.min() and ev.max() <= b + 1e-12
+
+
+@pytest.mark.parametrize("n", [8, 12])
+def test_cheb_apply_on_fourier_modes(ora, n):
+    """Constant coefficients: every Fourier mode is an eigenvector of D^-1 M
+    (eigenvalue lambda = FFT eigenvalue / D), so the preconditioner maps a
+    random field r to the inverse FFT of p(lambda) r_hat / D."""
+    rng = np.random.default_rng(n + 1)
+    psidt, kappa = 3.7, 0.11
+    P = np.full((n, n, n), psidt)
+    K = [np.full((n, n, n), kappa) for _ in range(3)]
+    D = psidt + 6 * kappa / (2 * math.pi / n) ** 2
+    c0, c1, a = ora.cheb_coef(P, K)
+    assert abs(a - psidt / D) <= 1e-15
+    lam = fft_eigs(n, psidt, kappa) / D
+    r = rng.standard_normal((n, n, n))
+    want = np.real(np.fft.ifftn((c0 + c1 * lam) * np.fft.fftn(r))) / D
+    z = ora.cheb_apply(P, K, r)
+    assert np.max(np.abs(z - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_pcg_cheb_solves_and_stops_like_pcg(ora, hit_system):
+    """Same solution as the dense solve; same stopping rule as Jacobi-PCG (a
+    start at the solution takes 0 iterations, maxit exhaustion reported); on
+    this system it needs no more iterations than Jacobi-PCG."""
+    s = hit_system
+    n = s["n"]
+    M = assemble(ora, s["psidt"], s["K"], n)
+    x_dense = np.linalg.solve(M, s["b"].ravel()).reshape(n, n, n)
+    xs, it, rel = ora.pcg_cheb(s["psidt"], s["K"], s["b"], tol=1e-14, maxit=1000)
+    assert it > 0 and np.max(np.abs(xs - x_dense)) <= 1e-12 * np.max(np.abs(x_dense))
+    _, it0, _ = ora.pcg_cheb(s["psidt"], s["K"], s["b"], x0=x_dense, tol=1e-8)
+    assert it0 == 0
+    _, itm, rel = ora.pcg_cheb(s["psidt"], s["K"], s["b"], tol=1e-14, maxit=1)
+    assert itm < 0
+    for tol in (1e-6, 1e-10):
+        assert ora.pcg_cheb(s["psidt"], s["K"], s["b"], tol=tol)[1] <= \
+            ora.pcg(s["psidt"], s["K"], s["b"], tol=tol)[1]
