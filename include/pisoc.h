@@ -183,9 +183,11 @@ enum {
                                        corrector 1's solve (s1 times its output) */
     PISOC_FIELD_GUESS_X0 = 1u << 11,/* captured, learned guess: that solve's start x0 =
                                        alpha g, alpha = g.b / g.(M g), or 0 on a fallback */
-    PISOC_FIELD_PSOLVE_W = 1u << 12 /* captured: w = rho/a_P, whose I4 face values are the
+    PISOC_FIELD_PSOLVE_W = 1u << 12,/* captured: w = rho/a_P, whose I4 face values are the
                                        operator's K_f (with diag, M is then known:
                                        psi/dt = diag - (1/h^2) sum_f K_f) */
+    PISOC_FIELD_PSOLVE_PSIDT = 1u << 13 /* captured: that psi/dt, formed from the captured
+                                           diag and w (for pisoc_helm_solve) */
 };
 
 /* Bytes of device workspace pisoc_init needs for these parameters (0 if the
@@ -381,6 +383,26 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
                               const double* d_b, double* d_x, double tol, int32_t maxit,
                               void* d_workspace, size_t ws_bytes, void* hip_stream,
                               int32_t* iters, double* relres);
+
+/* Preconditioners of pisoc_helm_solve_precond. */
+enum {
+    PISOC_PRECOND_JACOBI = 0, /* z = D^-1 r, D = diag(M): the solve of the step */
+    PISOC_PRECOND_CHEB = 1    /* z = p(D^-1 M) D^-1 r, a degree-1 Chebyshev polynomial */
+};
+
+/* pisoc_helm_solve with a choice of preconditioner: a non-learned rival of the
+ * learned initial guess (not in the paper).  PISOC_PRECOND_CHEB: the spectrum
+ * of D^-1 M lies in [a, 2 - a], a = min psidt/diag (Gershgorin); p is the
+ * degree-1 polynomial whose residual 1 - lambda p(lambda) is the degree-2
+ * Chebyshev polynomial of that interval normalised to 1 at 0 (positive on the
+ * interval, so the preconditioner is symmetric positive definite).  Each
+ * iteration applies M twice (two launches).  Arguments, stopping rule,
+ * workspace and results as pisoc_helm_solve; another precond value is
+ * PISOC_ERR_INVALID.  Synchronises. */
+pisoc_status pisoc_helm_solve_precond(int32_t n, const double* d_psidt, const double* d_w,
+                                      const double* d_b, double* d_x, double tol, int32_t maxit,
+                                      int32_t precond, void* d_workspace, size_t ws_bytes,
+                                      void* hip_stream, int32_t* iters, double* relres);
 
 /* The pressure solve of pisoc_helm_solve for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses

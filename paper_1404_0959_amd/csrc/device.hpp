@@ -39,6 +39,7 @@ struct PcgState {
     double tol2;      // tol^2 of the current (inner) solve
     double tol_final; // p_tol^2: the requested relative residual, squared
     double alphah[2]; // alpha_{k-1}, written by CG iteration k in slot k & 1
+    double cheb[2];   // c0, c1 of the Chebyshev polynomial preconditioner
     int32_t it_stop;  // iteration index at which the solve stopped (kIterInf: running)
     int32_t maxit;
     int32_t iters;

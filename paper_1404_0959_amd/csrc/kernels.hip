@@ -1511,6 +1511,164 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     block_partials<CG_COLS, 0u>(acc, part_out);
 }
 
+// ---- CG preconditioned by a Chebyshev polynomial (stand-alone solve) ----
+// A non-learned rival of the learned guess: z = p(D^-1 M) D^-1 r with the
+// degree-1 p whose residual polynomial 1 - lambda p(lambda) is the degree-2
+// Chebyshev polynomial of [a, 2 - a], a = min psi/dt / diag (the Gershgorin
+// interval of D^-1 M): p(lambda) = c0 + c1 lambda,
+//   mu = (b + a)/(b - a), T2 = 2 mu^2 - 1, c0 = 8 mu / ((b - a) T2),
+//   c1 = -8 / ((b - a)^2 T2),  b = 2 - a.
+// Two launches per iteration k: k_cheb_res forms r_k = r_{k-1} - alpha q_{k-1}
+// and x_k, then z_k (a stencil over t = r_k / diag); k_cheb_dir tests r_k,
+// forms p_k = z_k + beta p_{k-1} and q_k = M p_k.  r and p alternate between
+// two buffers (the stencils read the previous iterate at the neighbours);
+// partial sums alternate between two column sets by k & 1.  M v is taken in
+// its diagonal form diag v - (1/h^2) sum_f K_f v_nb.
+
+// Largest -psi/dt / diag over the cells (the interval's lower end a).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cheb_theta(Phys ph, const T* __restrict__ psidt,
+                                                       const T* __restrict__ diag, double* part) {
+    MEMBER(ph)
+    double v[1] = {-__builtin_inf()};
+    FOR_CELLS(ph)
+    const double t = -(double)psidt[P] / (double)diag[P];
+    v[0] = t > v[0] ? t : v[0];
+    END_CELLS
+    block_partials<1, 1u>(v, part);
+}
+
+template <typename T>
+__device__ inline T m_diag_form(const T* __restrict__ diag, const T* __restrict__ w, const CellIdx& c,
+                                T inv_h2, T vP, const T (&nb)[6]) {
+    T s = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s += i4(w, c, d, 0) * nb[2 * d] + i4(w, c, d, -1) * nb[2 * d + 1];
+    return diag[c.self()] * vP - s * inv_h2;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cheb_res(Phys ph, DevState* st, int k,
+                                                     const T* __restrict__ rin, T* __restrict__ rout,
+                                                     const T* __restrict__ q, const T* __restrict__ p,
+                                                     const T* __restrict__ diag, const T* __restrict__ w,
+                                                     T* __restrict__ x, T* __restrict__ z,
+                                                     const double* part_theta, unsigned nb_theta,
+                                                     const double* part_prev, double* part_out) {
+    MEMBER(ph)
+    PcgState& g = (st + mem_)->pcg;
+    if (k > g.it_stop) return;
+    double c0, c1, alpha = 0.0;
+    if (k == 0) {
+        double t[1];
+        reduce_member<1, 1u>(part_theta, nb_theta, ph.batch, mem_, t);
+        const double a = -t[0], b = 2.0 - a, mu = (b + a) / (b - a), t2 = 2.0 * mu * mu - 1.0;
+        c0 = 8.0 * mu / ((b - a) * t2);
+        c1 = -8.0 / ((b - a) * (b - a) * t2);
+        if (MEMBER_FIRST()) {
+            g.cheb[0] = c0;
+            g.cheb[1] = c1;
+        }
+    } else {
+        c0 = g.cheb[0];
+        c1 = g.cheb[1];
+        double t[kChebSet];
+        reduce_member<kChebSet, 0u>(part_prev, num_blocks(), ph.batch, mem_, t);
+        alpha = t[kChebRes] / t[kChebDir];
+    }
+    const T al = (T)alpha, inv_h2 = (T)ph.inv_h2;
+    double v[2] = {0.0, 0.0};
+    FOR_CELLS(ph)
+    auto res = [&](size_t Q) -> T { return k == 0 ? rin[Q] : rin[Q] - al * q[Q]; };
+    auto tv = [&](size_t Q) -> T { return res(Q) / diag[Q]; };
+    const T rP = res(P), tP = rP / diag[P];
+    const T nb[6] = {tv(c.sh(0, 1)), tv(c.sh(0, -1)), tv(c.sh(1, 1)), tv(c.sh(1, -1)),
+                     tv(c.sh(2, 1)), tv(c.sh(2, -1))};
+    const T Mt = m_diag_form(diag, w, c, inv_h2, tP, nb);
+    const T zP = (T)c0 * tP + (T)c1 * Mt / diag[P];
+    if (k > 0) {
+        x[P] += al * p[P];
+        rout[P] = rP;
+    }
+    z[P] = zP;
+    v[0] += (double)rP * (double)zP;
+    v[1] += (double)rP * (double)rP;
+    END_CELLS
+    block_partials<2, 0u>(v, part_out + kChebRes * (size_t)num_blocks());
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cheb_dir(Phys ph, DevState* st, int k,
+                                                     const T* __restrict__ z, const T* __restrict__ pin,
+                                                     T* __restrict__ pout, T* __restrict__ q,
+                                                     const T* __restrict__ diag, const T* __restrict__ w,
+                                                     const double* part_u, unsigned nb_u,
+                                                     const double* part_prev, double* part_cur,
+                                                     int maxit) {
+    MEMBER(ph)
+    PcgState& g = (st + mem_)->pcg;
+    if (k > g.it_stop) return;
+    double t[kChebSet];
+    reduce_member<kChebSet, 0u>(part_cur, num_blocks(), ph.batch, mem_, t);
+    double bb;
+    if (k == 0) {
+        double u[3];
+        reduce_member<3, 0u>(part_u, nb_u, ph.batch, mem_, u);
+        bb = u[2];
+    } else {
+        bb = g.bb;
+    }
+    const double rr = t[kChebRes + 1];
+    const bool conv = rr <= g.tol2 * bb;
+    const bool stop = conv || k >= maxit;
+    if (MEMBER_FIRST()) {
+        if (k == 0) g.bb = bb;
+        g.rr = rr;
+        g.iters = k;
+        if (stop) {
+            g.it_stop = k;
+            g.converged = conv ? 1 : 0;
+        }
+    }
+    if (stop) return;
+    double beta = 0.0;
+    if (k > 0) {
+        double tp[kChebSet];
+        reduce_member<kChebSet, 0u>(part_prev, num_blocks(), ph.batch, mem_, tp);
+        beta = t[kChebRes] / tp[kChebRes];
+    }
+    const T be = (T)beta, inv_h2 = (T)ph.inv_h2;
+    double v[1] = {0.0};
+    FOR_CELLS(ph)
+    auto dir = [&](size_t Q) -> T { return k == 0 ? z[Q] : z[Q] + be * pin[Q]; };
+    const T pP = dir(P);
+    const T nb[6] = {dir(c.sh(0, 1)), dir(c.sh(0, -1)), dir(c.sh(1, 1)), dir(c.sh(1, -1)),
+                     dir(c.sh(2, 1)), dir(c.sh(2, -1))};
+    const T qP = m_diag_form(diag, w, c, inv_h2, pP, nb);
+    pout[P] = pP;
+    q[P] = qP;
+    v[0] += (double)pP * (double)qP;
+    END_CELLS
+    block_partials<1, 0u>(v, part_cur + kChebDir * (size_t)num_blocks());
+}
+
+// psi/dt of a captured pressure system from its diagonal and w:
+// psi/dt = diag - (1/h^2) sum_f I4(w)_f (one grid of n^3 FP64 values).
+__global__ void __launch_bounds__(kBlock) k_psidt_of(int n, double inv_h2,
+                                                     const double* __restrict__ diag,
+                                                     const double* __restrict__ w,
+                                                     double* __restrict__ out) {
+    const size_t N = (size_t)n * n * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const CellIdx c(n, (int)(i % n), (int)((i / n) % n), (int)(i / ((size_t)n * n)), 0);
+        double sumK = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sumK += i4(w, c, d, 0) + i4(w, c, d, -1);
+        out[i] = diag[i] - sumK * inv_h2;
+    }
+}
+
 // y = M x for the stand-alone operator entry point (psi/dt given as a field).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_helm_apply(Phys ph, const T* __restrict__ psidt,
@@ -2986,6 +3144,12 @@ static dim3 lin_grid(size_t count) {
 
 #define LAUNCH(kern, L, s, ...) hipLaunchKernelGGL(kern, L.grid, L.block, 0, s, __VA_ARGS__)
 
+void psidt_of(hipStream_t s, int n, const double* diag, const double* w, double* out) {
+    const double h = 2.0 * M_PI / n;
+    const size_t N = (size_t)n * n * n;
+    hipLaunchKernelGGL(k_psidt_of, lin_grid(N), dim3(kBlock), 0, s, n, 1.0 / (h * h), diag, w, out);
+}
+
 template <typename T>
 void Ops<T>::cast_in(hipStream_t s, const double* src, T* dst, size_t count, double shift) {
     hipLaunchKernelGGL(k_cast_in<T>, lin_grid(count), dim3(kBlock), 0, s, src, dst, count, shift);
@@ -3164,6 +3328,26 @@ template <typename T>
 void Ops<T>::helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt, const T* w,
                         const T* x, T* y) {
     LAUNCH(k_helm_apply<T>, L, s, ph, psidt, w, x, y);
+}
+template <typename T>
+void Ops<T>::cheb_theta(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt, const T* diag,
+                        double* part) {
+    LAUNCH(k_cheb_theta<T>, L, s, ph, psidt, diag, part);
+}
+template <typename T>
+void Ops<T>::cheb_res(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int k,
+                      const T* rin, T* rout, const T* q, const T* p, const T* diag, const T* w, T* x,
+                      T* z, const double* part_theta, unsigned nb_theta, const double* part_prev,
+                      double* part_out) {
+    LAUNCH(k_cheb_res<T>, L, s, ph, st, k, rin, rout, q, p, diag, w, x, z, part_theta, nb_theta,
+           part_prev, part_out);
+}
+template <typename T>
+void Ops<T>::cheb_dir(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int k, const T* z,
+                      const T* pin, T* pout, T* q, const T* diag, const T* w, const double* part_u,
+                      unsigned nb_u, const double* part_prev, double* part_cur, int maxit) {
+    LAUNCH(k_cheb_dir<T>, L, s, ph, st, k, z, pin, pout, q, diag, w, part_u, nb_u, part_prev, part_cur,
+           maxit);
 }
 template <typename T>
 void Ops<T>::helm_start(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,

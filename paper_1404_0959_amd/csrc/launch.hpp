@@ -52,8 +52,14 @@ constexpr int kSmallTX = 16;
 constexpr int kRowCells = 4, kRowWaves = 8, kRowBlocks = 256;
 Launch make_spmv_launch(int n, int batch, int elem_bytes, int cz_tile = 0);
 
+// psi/dt = diag - (1/h^2) sum_f I4(w)_f of a captured pressure system (n^3 FP64).
+void psidt_of(hipStream_t s, int n, const double* diag, const double* w, double* out);
+
 // Partial-sum columns written by one CG iteration.
 constexpr int kCgCols = 7;
+// Chebyshev-preconditioned CG: one set of columns per iteration (r.z, r.r,
+// p.q), sets alternating by k & 1 from PS_CG, the interval's end after them.
+constexpr int kChebRes = 0, kChebDir = 2, kChebSet = 3;
 
 // Partial-sum slots in the workspace (columns of num_blocks doubles each).
 enum PartSlot {
@@ -143,6 +149,19 @@ struct Ops {
                          DevState* st, int k, const CgArgs<T>& a);
     static void helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt,
                            const T* w, const T* x, T* y);
+    // CG preconditioned by a Chebyshev polynomial (stand-alone solve): the
+    // interval's lower end, then per iteration the residual/preconditioner and
+    // the direction/operator launches
+    static void cheb_theta(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt,
+                           const T* diag, double* part);
+    static void cheb_res(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int k,
+                         const T* rin, T* rout, const T* q, const T* p, const T* diag, const T* w,
+                         T* x, T* z, const double* part_theta, unsigned nb_theta,
+                         const double* part_prev, double* part_out);
+    static void cheb_dir(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int k,
+                         const T* z, const T* pin, T* pout, T* q, const T* diag, const T* w,
+                         const double* part_u, unsigned nb_u, const double* part_prev,
+                         double* part_cur, int maxit);
     static void helm_start(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                            const T* psidt, const T* w, const T* b, const T* x, T* r, T* diag,
                            double* part_u);

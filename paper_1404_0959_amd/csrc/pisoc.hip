@@ -1343,6 +1343,13 @@ pisoc_status member_fields(pisoc_ctx* ctx, int m, uint32_t which, double* const*
                     Ops<float>::pressure_out(s, ctx->ph, ctx->rho_ref[m], ctx->p_ref[m],
                                              ctx->f<float>(ctx->rn) + off, dst);
                 break;
+            case PISOC_FIELD_PSOLVE_PSIDT:
+                if (!snap) {
+                    ctx->err = "captured pressure system requested without params.capture";
+                    return PISOC_ERR_INVALID;
+                }
+                psidt_of(s, ctx->prm.n, snap + NT + off, snap + 4 * NT + off, dst);
+                break;
             case PISOC_FIELD_PSOLVE_B:
             case PISOC_FIELD_PSOLVE_DIAG:
             case PISOC_FIELD_P_PREV:
@@ -2403,10 +2410,43 @@ pisoc_status pisoc_helm_apply(int32_t n, const double* d_psidt, const double* d_
 
 // The solve of pisoc_helm_solve on the workspace ws (laid out as lay), with
 // hst a host DevState the state is read back into.
+// CG preconditioned by the Chebyshev polynomial on the system helm_start set
+// up: per iteration k one residual/preconditioner and one direction/operator
+// launch, in batches of 16 iterations with a host wait after each until the
+// solve has stopped (at the tolerance or at maxit).
+static pisoc_status run_cheb(pisoc_ctx* ctx, const double* psidt, const double* w,
+                             const double* diag, double* const r[2], double* const p[2], double* z,
+                             double* q, double* x, int maxit) {
+    using O = Ops<double>;
+    const Launch& L = ctx->L;
+    const unsigned nb = L.nblocks;
+    hipStream_t s = ctx->stream;
+    double* theta = ctx->part(PS_CG + 2 * kChebSet);
+    O::cheb_theta(L, s, ctx->ph, psidt, diag, theta);
+    for (int k = 0;;) {
+        const int kend = std::min(k + 15, maxit);
+        for (int kk = k; kk <= kend; ++kk) {
+            double* cur = ctx->part(PS_CG + kChebSet * (kk & 1));
+            double* prev = ctx->part(PS_CG + kChebSet * ((kk + 1) & 1));
+            double* rin = r[kk == 0 ? 0 : (kk - 1) & 1];
+            double* pin = p[(kk + 1) & 1];
+            O::cheb_res(L, s, ctx->ph, ctx->st, kk, rin, r[kk & 1], q, pin, diag, w, x, z, theta, nb,
+                        prev, cur);
+            O::cheb_dir(L, s, ctx->ph, ctx->st, kk, z, pin, p[kk & 1], q, diag, w, ctx->part(PS_U), nb,
+                        prev, cur, maxit);
+        }
+        pisoc_status st = sync_state(ctx);
+        if (st != PISOC_OK) return st;
+        if (ctx->hst->pcg.it_stop != kIterInf) return PISOC_OK;
+        k = kend + 1;
+    }
+}
+
 static pisoc_status helm_solve_on(int32_t n, const double* d_psidt, const double* d_w,
                                   const double* d_b, double* d_x, double tol, int32_t maxit,
                                   char* ws, const Layout& lay, DevState* hst, hipStream_t stream,
-                                  int32_t* iters, double* relres) {
+                                  int32_t* iters, double* relres,
+                                  int32_t precond = PISOC_PRECOND_JACOBI) {
     pisoc_ctx ctx{};
     ctx.prm = plain_params(n);
     ctx.prm.p_maxit = maxit;
@@ -2448,7 +2488,13 @@ static pisoc_status helm_solve_on(int32_t n, const double* d_psidt, const double
         v.x = d_x;
         v.diag = dg;
         v.w = const_cast<double*>(d_w);
-        st = run_pcg<double>(&ctx, v, true, 16, true, nullptr, false, ctx.L.nblocks);
+        if (precond == PISOC_PRECOND_CHEB) {
+            double* const rr[2] = {v.r[0], v.r[1]};
+            double* const pp[2] = {v.p[0], v.p[1]};
+            st = run_cheb(&ctx, d_psidt, d_w, dg, rr, pp, v.p[2], v.q[0], d_x, maxit);
+        } else {
+            st = run_pcg<double>(&ctx, v, true, 16, true, nullptr, false, ctx.L.nblocks);
+        }
         if (st == PISOC_OK) {
             const PcgState& g = ctx.hst->pcg;
             if (iters) *iters = g.iters;
@@ -2465,8 +2511,17 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
                               const double* d_b, double* d_x, double tol, int32_t maxit,
                               void* d_workspace, size_t ws_bytes, void* hip_stream,
                               int32_t* iters, double* relres) {
+    return pisoc_helm_solve_precond(n, d_psidt, d_w, d_b, d_x, tol, maxit, PISOC_PRECOND_JACOBI,
+                                    d_workspace, ws_bytes, hip_stream, iters, relres);
+}
+
+pisoc_status pisoc_helm_solve_precond(int32_t n, const double* d_psidt, const double* d_w,
+                                      const double* d_b, double* d_x, double tol, int32_t maxit,
+                                      int32_t precond, void* d_workspace, size_t ws_bytes,
+                                      void* hip_stream, int32_t* iters, double* relres) {
     if (n < PISOC_MIN_N || n > PISOC_MAX_N || !d_psidt || !d_w || !d_b || !d_x ||
-        !(tol > 0.0) || !(tol < 1.0) || maxit < 1)
+        !(tol > 0.0) || !(tol < 1.0) || maxit < 1 ||
+        (precond != PISOC_PRECOND_JACOBI && precond != PISOC_PRECOND_CHEB))
         return PISOC_ERR_INVALID;
     const Layout lay = helm_layout(n);
     if (!d_workspace || ws_bytes < lay.total ||
@@ -2478,7 +2533,7 @@ pisoc_status pisoc_helm_solve(int32_t n, const double* d_psidt, const double* d_
         return PISOC_ERR_HIP;
     const pisoc_status st =
         helm_solve_on(n, d_psidt, d_w, d_b, d_x, tol, maxit, reinterpret_cast<char*>(d_workspace),
-                      lay, hst, reinterpret_cast<hipStream_t>(hip_stream), iters, relres);
+                      lay, hst, reinterpret_cast<hipStream_t>(hip_stream), iters, relres, precond);
     (void)hipHostFree(hst);
     return st;
 }

@@ -27,11 +27,13 @@ FLAG_DUST_NEG, FLAG_DUST_NONFINITE, FLAG_DUST_DIAG, FLAG_DUST_COURANT = 64, 128,
 FIELD_RHO, FIELD_U, FIELD_PHI, FIELD_RHO_P, FIELD_P = 1, 2, 4, 8, 16
 FIELD_PSOLVE_B, FIELD_PSOLVE_X, FIELD_P_PREV, FIELD_PSOLVE_DIAG = 32, 64, 128, 256
 FIELD_USTAR, FIELD_GUESS, FIELD_GUESS_X0, FIELD_PSOLVE_W = 512, 1024, 2048, 4096
+FIELD_PSOLVE_PSIDT = 8192
 
 EXPORTED = [
     "pisoc_workspace_bytes", "pisoc_init", "pisoc_step", "pisoc_fields", "pisoc_get_stats",
     "pisoc_time", "pisoc_steps_done", "pisoc_destroy", "pisoc_last_error", "pisoc_status_string",
     "pisoc_helm_apply", "pisoc_helm_workspace_bytes", "pisoc_helm_solve",
+    "pisoc_helm_solve_precond",
     "pisoc_helm_solve_noalloc",
     "pisoc_profile", "pisoc_profile_read",
     "pisoc_net_workspace_bytes", "pisoc_net_forward", "pisoc_net_grad", "pisoc_net_adam",
@@ -137,6 +139,9 @@ def lib():
     L.pisoc_helm_solve.argtypes = [i32, vp, vp, vp, vp, f64, i32, vp, sz, vp,
                                    C.POINTER(i32), C.POINTER(f64)]
     L.pisoc_helm_solve.restype = C.c_int
+    L.pisoc_helm_solve_precond.argtypes = [i32, vp, vp, vp, vp, f64, i32, i32, vp, sz, vp,
+                                           C.POINTER(i32), C.POINTER(f64)]
+    L.pisoc_helm_solve_precond.restype = C.c_int
     L.pisoc_helm_solve_noalloc.argtypes = [i32, vp, vp, vp, vp, f64, i32, vp,
                                            C.POINTER(i32), C.POINTER(f64)]
     L.pisoc_helm_solve_noalloc.restype = C.c_int
@@ -311,7 +316,7 @@ class Solver:
                   FIELD_PSOLVE_B: (n, n, n), FIELD_PSOLVE_X: (n, n, n),
                   FIELD_P_PREV: (n, n, n), FIELD_PSOLVE_DIAG: (n, n, n),
                   FIELD_USTAR: (3, n, n, n), FIELD_GUESS: (n, n, n), FIELD_GUESS_X0: (n, n, n),
-                  FIELD_PSOLVE_W: (n, n, n)}
+                  FIELD_PSOLVE_W: (n, n, n), FIELD_PSOLVE_PSIDT: (n, n, n)}
         bits = [b for b in sorted(shapes) if which & b]
         outs = [torch.empty(shapes[b], dtype=torch.float64, device=self.device) for b in bits]
         arr = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
@@ -454,7 +459,7 @@ class Ensemble:
                   FIELD_PSOLVE_B: (n, n, n), FIELD_PSOLVE_X: (n, n, n),
                   FIELD_P_PREV: (n, n, n), FIELD_PSOLVE_DIAG: (n, n, n),
                   FIELD_USTAR: (3, n, n, n), FIELD_GUESS: (n, n, n), FIELD_GUESS_X0: (n, n, n),
-                  FIELD_PSOLVE_W: (n, n, n)}
+                  FIELD_PSOLVE_W: (n, n, n), FIELD_PSOLVE_PSIDT: (n, n, n)}
         bits = [b for b in sorted(shapes) if which & b]
         outs = [torch.empty(shapes[b], dtype=torch.float64, device=self.device) for b in bits]
         arr = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
@@ -578,8 +583,9 @@ def helm_apply(psidt, w, x, stream=None):
     return y
 
 
-def helm_solve(psidt, w, b, x0=None, tol=1e-10, maxit=1000, stream=None):
-    """Jacobi-PCG on M x = b; returns (x, iterations, relres, status)."""
+def helm_solve(psidt, w, b, x0=None, tol=1e-10, maxit=1000, stream=None, precond=None):
+    """Preconditioned CG on M x = b (Jacobi, or PRECOND_CHEB); returns
+    (x, iterations, relres, status)."""
     torch = _torch()
     n = b.shape[-1]
     x = torch.zeros_like(b) if x0 is None else x0.clone()
@@ -587,14 +593,21 @@ def helm_solve(psidt, w, b, x0=None, tol=1e-10, maxit=1000, stream=None):
     ws = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
     it = C.c_int32(0)
     rel = C.c_double(0.0)
-    st = lib().pisoc_helm_solve(n, psidt.data_ptr(), w.data_ptr(), b.data_ptr(), x.data_ptr(),
-                                tol, maxit, ws.data_ptr(), nbytes, _stream_ptr(torch, stream),
-                                C.byref(it), C.byref(rel))
+    if precond is None:
+        st = lib().pisoc_helm_solve(n, psidt.data_ptr(), w.data_ptr(), b.data_ptr(), x.data_ptr(),
+                                    tol, maxit, ws.data_ptr(), nbytes, _stream_ptr(torch, stream),
+                                    C.byref(it), C.byref(rel))
+    else:
+        st = lib().pisoc_helm_solve_precond(n, psidt.data_ptr(), w.data_ptr(), b.data_ptr(),
+                                            x.data_ptr(), tol, maxit, precond, ws.data_ptr(),
+                                            nbytes, _stream_ptr(torch, stream), C.byref(it),
+                                            C.byref(rel))
     if st < 0:
         raise PisocError(st, "pisoc_helm_solve")
     return x, it.value, rel.value, st
 
 
+PRECOND_JACOBI, PRECOND_CHEB = 0, 1
 HELM_NOALLOC_MAX_N = 64
 
 

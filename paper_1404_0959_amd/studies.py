@@ -3,6 +3,7 @@
     python -m paper_1404_0959_amd.studies precision [--n 256] [--steps 200]
     python -m paper_1404_0959_amd.studies stats [--n 128] [--steps 500]
     python -m paper_1404_0959_amd.studies stokes [--n 128] [--steps 500] [--mach 0.5]
+    python -m paper_1404_0959_amd.studies rivals [--steps 4]
 
 precision: the FP32 mode (FP32 fields and inner CG, FP64 residual
 refinement, reductions and mass budget) against plain FP64 on the same seeded
@@ -25,6 +26,10 @@ flags first rise (negative bulk density, non-positive implicit diagonal, the
 dust's Courant number past the transport update's stability bound),
 the concentration variance over time and the smallest relative dust density,
 which bound the Stokes range where the transport reading stays usable.
+
+rivals: the learned guess against the Chebyshev-polynomial preconditioner on
+the same captured pressure systems at 32^3, 128^3 and 256^3 (iterations and
+time per solve, and the network's time per application).
 """
 from __future__ import annotations
 
@@ -158,9 +163,62 @@ def stokes_range(n=128, steps=500, every=10, seed=0, p_tol=1e-8, mach=0.5,
     return dict(n=n, steps=steps, every=every, mach=mach, seed=seed, runs=out)
 
 
+def rivals(sizes=(32, 128, 256), steps=4, seed=20, p_tol=1e-6, reps=3, log=print):
+    """The learned guess against a non-learned rival on the same systems: the
+    first corrector's pressure system of step `steps` of a run with the
+    learned guess (FP64, Mach 0.2, Stokes 0.2) is solved again stand-alone to
+    the same residual with Jacobi-PCG and with the Chebyshev-polynomial
+    preconditioner, each from zero and from the learned guess's start x0:
+    iterations and wall time per solve (best of reps), beside the time of one
+    network application on a grid of that size."""
+    import math
+
+    import torch
+
+    from .learn import load_weights
+    wts = load_weights()
+    out = []
+    for n in sizes:
+        case = make_hit_case(n, seed, mach=0.2, stokes=(0.2,))
+        s = P.Solver.from_case(case, p_tol=p_tol, capture=True, guess=P.GUESS_LEARNED,
+                               guess_weights=wts.data_ptr())
+        st, info = s.step(steps)
+        f = s.fields(P.FIELD_PSOLVE_B | P.FIELD_PSOLVE_PSIDT | P.FIELD_PSOLVE_W |
+                     P.FIELD_GUESS_X0)
+        s.close()
+        b, psidt, w = f[P.FIELD_PSOLVE_B], f[P.FIELD_PSOLVE_PSIDT], f[P.FIELD_PSOLVE_W]
+        x0 = f[P.FIELD_GUESS_X0]
+        row = dict(n=n, step=steps, fallback=bool(float(x0.abs().max()) == 0.0),
+                   in_step_iters=info[-1]["pcg_iters"][0])
+        for name, pc in (("jacobi", P.PRECOND_JACOBI), ("cheb", P.PRECOND_CHEB)):
+            for start, xs in (("zero", None), ("learned", x0)):
+                best, it = math.inf, None
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, it, rel, stt = P.helm_solve(psidt, w, b, x0=xs, tol=p_tol, maxit=1000,
+                                                   precond=pc)
+                    torch.cuda.synchronize()
+                    best = min(best, time.perf_counter() - t0)
+                row[f"{name}_{start}"] = dict(iters=it, ms=round(best * 1e3, 3))
+        net = P.Net(n, 1)
+        xin = torch.zeros(1, n ** 3, 2, dtype=torch.float32, device="cuda")
+        best = math.inf
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            net.forward(wts, xin)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        row["network_ms"] = round(best * 1e3, 3)
+        log(json.dumps(row))
+        out.append(row)
+    return dict(seed=seed, p_tol=p_tol, runs=out)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["precision", "stats", "stokes"])
+    ap.add_argument("what", choices=["precision", "stats", "stokes", "rivals"])
     ap.add_argument("--mach", type=float, default=0.5)
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--steps", type=int, default=None)
@@ -172,6 +230,8 @@ def main():
         print(m, file=sys.stderr, flush=True)
     if args.what == "precision":
         r = precision(n=args.n or 256, steps=args.steps or 200, every=args.every, log=log)
+    elif args.what == "rivals":
+        r = rivals(steps=args.steps or 4, log=log)
     elif args.what == "stokes":
         r = stokes_range(n=args.n or 128, steps=args.steps or 500, every=args.every,
                          mach=args.mach, log=log)

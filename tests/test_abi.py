@@ -96,6 +96,17 @@ def test_workspace_checked_before_gpu_work(lib):
                                 None, None) == P.ERR_INVALID
 
 
+def test_precond_solve_rejects_before_gpu_work(lib):
+    """An unknown preconditioner is an invalid argument; a known one still
+    checks its workspace first (no device is touched here)."""
+    dummy = ctypes.c_void_p(256)
+    assert lib.pisoc_helm_solve_precond(32, dummy, dummy, dummy, dummy, 1e-8, 10, 7, dummy,
+                                        1 << 30, None, None, None) == P.ERR_INVALID
+    for pc in (P.PRECOND_JACOBI, P.PRECOND_CHEB):
+        assert lib.pisoc_helm_solve_precond(32, dummy, dummy, dummy, dummy, 1e-8, 10, pc, None,
+                                            0, None, None, None) == P.ERR_WORKSPACE
+
+
 def test_status_strings(lib):
     for st in (0, 1, 2, 3, -1, -2, -3, -4):
         assert lib.pisoc_status_string(st)

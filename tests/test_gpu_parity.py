@@ -125,6 +125,45 @@ def test_helm_solve_parity(P, ora, n):
     assert np.max(np.abs(to_np(xg) - xo)) <= 1e-12 * np.max(np.abs(xo))
 
 
+@pytest.mark.parametrize("n", [16, 40, 128])
+def test_helm_solve_cheb_parity(P, ora, n):
+    """CG with the Chebyshev polynomial preconditioner against the oracle's:
+    the same iteration count, relative residual and solution; fewer
+    iterations than Jacobi-PCG on the same system; the edge cases of the
+    stopping rule."""
+    import torch
+    rng = np.random.default_rng(200 + n)
+    h = 2 * math.pi / n
+    w = 0.01 * (1.0 + 0.2 * rng.random((n, n, n)))
+    # psi/dt against sum K / h^2 about 1 : 2 (psi/dt / diag near 1/3, where a
+    # solve takes tens of iterations at every n)
+    psidt = 3.0 * 0.01 / h ** 2 * (1.0 + 0.2 * rng.random((n, n, n)))
+    b = rng.standard_normal((n, n, n))
+    K = ora.kfaces(w)
+    xo, it_o, rel_o = ora.pcg_cheb(psidt, K, b, tol=1e-10, maxit=500)
+    d = lambda a: torch.as_tensor(a, device="cuda")
+    xg, it_g, rel_g, st = P.helm_solve(d(psidt), d(w), d(b), tol=1e-10, maxit=500,
+                                       precond=P.PRECOND_CHEB)
+    it_j = ora.pcg(psidt, K, b, tol=1e-10, maxit=500)[1]
+    print(f"{n}^3: Chebyshev {it_g} (oracle {it_o}), Jacobi {it_j}")
+    assert st == P.OK and it_o > 3 and it_o < it_j
+    assert it_g == it_o, (it_g, it_o)
+    assert abs(rel_g - rel_o) <= 1e-3 * rel_o
+    assert np.max(np.abs(to_np(xg) - xo)) <= 1e-12 * np.max(np.abs(xo))
+    if n == 16:
+        x, it, rel, st = P.helm_solve(d(psidt), d(w), d(np.zeros((n, n, n))), tol=1e-8,
+                                      precond=P.PRECOND_CHEB)
+        assert st == P.OK and it == 0 and float(x.abs().max()) == 0.0
+        x, it, rel, st = P.helm_solve(d(psidt), d(w), d(b), x0=d(xo), tol=1e-8,
+                                      precond=P.PRECOND_CHEB)
+        assert st == P.OK and it == 0
+        x, it, rel, st = P.helm_solve(d(psidt), d(w), d(b), tol=1e-14, maxit=3,
+                                      precond=P.PRECOND_CHEB)
+        xo3, it_o3, _ = ora.pcg_cheb(psidt, K, b, tol=1e-14, maxit=3)
+        assert st == P.WARN_NOT_CONVERGED and it == 3 and it_o3 < 0
+        assert np.max(np.abs(to_np(x) - xo3)) <= 1e-12 * np.max(np.abs(xo3))
+
+
 def test_helm_solve_edges(P, ora):
     import torch
     n = 16
@@ -269,9 +308,11 @@ def test_captured_pressure_system_parity(P, ora):
     s = P.Solver.from_case(case, p_tol=1e-8, capture=True)
     o.step(2)
     s.step(2)
-    f = s.fields(P.FIELD_PSOLVE_B | P.FIELD_PSOLVE_X | P.FIELD_P_PREV | P.FIELD_PSOLVE_DIAG)
+    f = s.fields(P.FIELD_PSOLVE_B | P.FIELD_PSOLVE_X | P.FIELD_P_PREV | P.FIELD_PSOLVE_DIAG |
+                 P.FIELD_PSOLVE_W | P.FIELD_PSOLVE_PSIDT)
     pairs = [(P.FIELD_PSOLVE_B, ora.SYS_B), (P.FIELD_PSOLVE_X, ora.SYS_X),
-             (P.FIELD_P_PREV, ora.SYS_P0), (P.FIELD_PSOLVE_DIAG, ora.SYS_DIAG)]
+             (P.FIELD_P_PREV, ora.SYS_P0), (P.FIELD_PSOLVE_DIAG, ora.SYS_DIAG),
+             (P.FIELD_PSOLVE_W, ora.SYS_W), (P.FIELD_PSOLVE_PSIDT, ora.SYS_PSIDT)]
     for fb, ob in pairs:
         print(f"captured system field {fb}: dev {raw_err(to_np(f[fb]), o.get(ob, corr=0))[0]:.2e}")
         assert dev_err(to_np(f[fb]), o.get(ob, corr=0)) <= TOL, fb
