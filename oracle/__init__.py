@@ -27,7 +27,8 @@ FLAG_PCG_MAXIT, FLAG_NONFINITE, FLAG_RHO_NONPOS, FLAG_KFACE_NONPOS = 1, 2, 4, 8
 FLAG_DUST_NEG, FLAG_DUST_NONFINITE, FLAG_DUST_DIAG, FLAG_DUST_COURANT = 64, 128, 256, 512
 DUST_COURANT_MAX = 0.638
 
-RHO, U, PHI, RHO_P, P = 0, 1, 2, 3, 4
+RHO, U, PHI, RHO_P, P, T = 0, 1, 2, 3, 4, 5
+BAROTROPIC, FOURIER = 0, 1
 SYS_B, SYS_W, SYS_PSIDT, SYS_K, SYS_X, SYS_P0, SYS_DIAG, SYS_USTAR = 10, 11, 12, 13, 14, 15, 16, 17
 
 STAT_KE, STAT_ENSTROPHY, STAT_RHO_RMS, STAT_MACH_RMS, STAT_MASS_GAS = 0, 1, 2, 3, 4
@@ -46,6 +47,8 @@ class OraParams(C.Structure):
         ("n_corr", C.c_int32), ("n_mom_sweeps", C.c_int32), ("n_dust_sweeps", C.c_int32),
         ("p_tol", C.c_double), ("p_maxit", C.c_int32),
         ("two_way", C.c_int32), ("gravity", C.c_double * 3),
+        ("closure", C.c_int32), ("R_gas", C.c_double), ("cv", C.c_double),
+        ("kappa", C.c_double), ("T0", C.c_double),
     ]
 
 
@@ -94,6 +97,8 @@ def lib():
         L.ora_destroy.restype = None
         L.ora_set_capture.argtypes = [C.c_void_p, C.c_int32]
         L.ora_set_capture.restype = None
+        L.ora_set_temperature.argtypes = [C.c_void_p, dp]
+        L.ora_set_temperature.restype = C.c_int
         L.ora_num_threads.argtypes = []
         L.ora_num_threads.restype = C.c_int
         L.ora_i4.argtypes = [C.c_int32, C.c_int32, dp, dp]
@@ -423,7 +428,9 @@ class Oracle:
     def __init__(self, n, rho, u, rho_p=None, *, gamma=1.4, C_=None, mu=1e-3, tau_p=(),
                  cfl=0.5, dt_growth=1.2, dt_fixed=0.0, dt_max=0.0, n_corr=2, n_mom_sweeps=4,
                  n_dust_sweeps=4, p_tol=1e-8, p_maxit=500, capture=False, two_way=False,
-                 gravity=(0.0, 0.0, 0.0)):
+                 gravity=(0.0, 0.0, 0.0), fourier=None, T=None):
+        """fourier: None (barotropic) or dict(R=, cv=, kappa=, T0=) for the ideal
+        gas with the energy equation; T: its initial temperature field."""
         if C_ is None:
             raise ValueError("closure constant C_ is required")
         tau_p = tuple(tau_p)
@@ -439,6 +446,10 @@ class Oracle:
         prm.two_way = 1 if two_way else 0
         for d in range(3):
             prm.gravity[d] = gravity[d]
+        if fourier is not None:
+            prm.closure = FOURIER
+            prm.R_gas, prm.cv, prm.kappa, prm.T0 = (fourier["R"], fourier["cv"], fourier["kappa"],
+                                                     fourier["T0"])
         self.prm = prm
         self.n = n
         self.K = len(tau_p)
@@ -452,6 +463,9 @@ class Oracle:
         self._h = h
         if capture:
             lib().ora_set_capture(h, 1)
+        if T is not None:
+            if lib().ora_set_temperature(h, _p(_f64(T).reshape(n, n, n))) != OK:
+                raise ValueError("ora_set_temperature needs the Fourier closure")
 
     @classmethod
     def from_case(cls, case, **kw):

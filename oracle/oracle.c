@@ -433,6 +433,8 @@ struct ora_state {
     double* rho_p[ORA_MAX_CLASSES];
     /* two-way: the dust mass fluxes of the last step, summed over the classes */
     double* fd[3];
+    /* Fourier closure: temperature */
+    double* T;
     /* captured pressure systems of the last step, one set per corrector */
     double* sys_b[ORA_MAX_CORR];
     double* sys_w[ORA_MAX_CORR];
@@ -455,6 +457,10 @@ static int check_params(const ora_params* p) {
     if (p->n < 4 || p->n > 1024) return 0;
     if (p->n_classes < 0 || p->n_classes > ORA_MAX_CLASSES) return 0;
     if (!(p->gamma > 1.0) || !(p->C > 0.0) || !(p->mu >= 0.0)) return 0;
+    if (p->closure != ORA_BAROTROPIC && p->closure != ORA_FOURIER) return 0;
+    if (p->closure == ORA_FOURIER &&
+        (!(p->R_gas > 0.0) || !(p->cv > 0.0) || !(p->kappa >= 0.0) || !(p->T0 > 0.0)))
+        return 0;
     if (p->n_corr < 1 || p->n_corr > ORA_MAX_CORR) return 0;
     if (p->n_mom_sweeps < 1 || p->n_dust_sweeps < 1) return 0;
     if (!(p->p_tol > 0.0) || p->p_maxit < 1) return 0;
@@ -467,6 +473,7 @@ static int check_params(const ora_params* p) {
 static void free_state(ora_state* s) {
     if (!s) return;
     free(s->rho);
+    free(s->T);
     for (int d = 0; d < 3; ++d) {
         free(s->u[d]);
         free(s->phi[d]);
@@ -538,7 +545,17 @@ int ora_create(const ora_params* prm, const double* rho, const double* u, const 
         memcpy(s->rho_p[c], rho_p + (size_t)c * s->N, s->N * sizeof(double));
     }
     initial_fluxes(s);
+    if (prm->closure == ORA_FOURIER) {
+        s->T = alloc_field(s->N);
+        for (size_t P = 0; P < s->N; ++P) s->T[P] = prm->T0;
+    }
     *out = s;
+    return ORA_OK;
+}
+
+int ora_set_temperature(ora_state* s, const double* T) {
+    if (!s || !T || s->p.closure != ORA_FOURIER) return ORA_ERR_INVALID;
+    memcpy(s->T, T, s->N * sizeof(double));
     return ORA_OK;
 }
 
@@ -671,7 +688,10 @@ static int one_step(ora_state* s, ora_info* info) {
             if (pr->two_way) src[d][P] += (rmn[P] - mean_m) * pr->gravity[d];
         }
     NEWF(pn);
-    for (size_t P = 0; P < N; ++P) pn[P] = Cc * pow(s->rho[P], g);
+    const int fourier = pr->closure == ORA_FOURIER;
+    const double Rg = pr->R_gas;
+    for (size_t P = 0; P < N; ++P)
+        pn[P] = fourier ? s->rho[P] * Rg * s->T[P] : Cc * pow(s->rho[P], g);
     NEWF(gp0); NEWF(gp1); NEWF(gp2);
     double* gpn[3] = {gp0, gp1, gp2};
     ora_grad(n, pn, gp0, gp1, gp2);
@@ -705,6 +725,47 @@ static int one_step(ora_state* s, ora_info* info) {
     if (s->capture)
         for (int d = 0; d < 3; ++d) keep(&s->sys_ustar[d], N, ucur[d]);
 
+    /* ---- 4b. Fourier closure: energy predictor.  The internal energy
+     * e = c_v T of the gas, backward Euler with the old mass fluxes (the
+     * momentum predictor's discretisation: I4 convection split into the
+     * diagonal (9/16) div(phi) and the rest, compact Laplacian for the heat
+     * flux q = -kappa grad T):
+     *   c_v [(rho* T - rho^n T^n)/dt + div(phi^n I4(T))] = -p^n div(u^n) + kappa Lap(T),
+     * solved by the same number of Jacobi sweeps from T^n.  The correctors
+     * then use p = rho R T* and psi = d rho / d p = 1/(R T*). ---- */
+    double* Ts = NULL;
+    if (fourier) {
+        const double cv = pr->cv, kap = pr->kappa;
+        NEWF(aT);
+        NEWF(sT);
+        NEWF(toff);
+        for (size_t P = 0; P < N; ++P) {
+            aT[P] = cv * (rhos[P] / dt + (9.0 / 16.0) * divphi[P]) + 6.0 * kap / (h * h);
+            sT[P] = cv * s->rho[P] * s->T[P] / dt - pn[P] * divu[P];
+        }
+        double* tcur = pool_get(s, slot++);
+        double* tnew = pool_get(s, slot++);
+        memcpy(tcur, s->T, N * sizeof(double));
+        for (int sweep = 0; sweep < pr->n_mom_sweeps; ++sweep) {
+            /* c_v times the convective off-diagonal part, minus the conduction's */
+            for (int d = 0; d < 3; ++d) {
+                ora_i4(n, d, tcur, tface[d]);
+                for (size_t P = 0; P < N; ++P) tface[d][P] *= s->phi[d][P];
+            }
+            ora_div_flux(n, tface[0], tface[1], tface[2], toff);
+            ora_lap(n, tcur, tlap);
+            for (size_t P = 0; P < N; ++P) {
+                double off = cv * (toff[P] - (9.0 / 16.0) * divphi[P] * tcur[P]) -
+                             kap * (tlap[P] + 6.0 * tcur[P] / (h * h));
+                tnew[P] = (sT[P] - off) / aT[P];
+            }
+            double* tmp = tcur;
+            tcur = tnew;
+            tnew = tmp;
+        }
+        Ts = tcur;
+    }
+
     /* ---- 5. PISO correctors ---- */
     NEWF(rhok);
     memcpy(rhok, rhos, N * sizeof(double));
@@ -724,8 +785,13 @@ static int one_step(ora_state* s, ora_info* info) {
     for (int corr = 0; corr < pr->n_corr; ++corr) {
         /* 5.1 pressure and compressibility of the current density iterate */
         for (size_t P = 0; P < N; ++P) {
-            p0[P] = Cc * pow(rhok[P], g);
-            psidt[P] = 1.0 / (g * Cc * pow(rhok[P], g - 1.0)) / dt;
+            if (fourier) {
+                p0[P] = rhok[P] * Rg * Ts[P];
+                psidt[P] = 1.0 / (Rg * Ts[P]) / dt;
+            } else {
+                p0[P] = Cc * pow(rhok[P], g);
+                psidt[P] = 1.0 / (g * Cc * pow(rhok[P], g - 1.0)) / dt;
+            }
         }
         /* 5.2 HbyA = H(u)/a_P with H(u) = s - N(u) */
         for (int d = 0; d < 3; ++d) {
@@ -881,6 +947,7 @@ static int one_step(ora_state* s, ora_info* info) {
     for (size_t P = 0; P < N; ++P)
         if (rhok[P] < rmin) rmin = rhok[P];
     if (!isfinite(m_gas) || !isfinite(usq)) flags |= ORA_FLAG_NONFINITE;
+    if (fourier && !isfinite(sum_field(n, Ts))) flags |= ORA_FLAG_NONFINITE;
     if (!(rmin > 0.0)) flags |= ORA_FLAG_RHO_NONPOS;
     info->dt = dt;
     info->courant = sigma * dt;
@@ -896,6 +963,7 @@ static int one_step(ora_state* s, ora_info* info) {
             status == ORA_OK)
             status = ORA_WARN_DUST;
         memcpy(s->rho, rhok, N * sizeof(double));
+        if (fourier) memcpy(s->T, Ts, N * sizeof(double));
         for (int d = 0; d < 3; ++d) {
             memcpy(s->u[d], ucur[d], N * sizeof(double));
             memcpy(s->phi[d], phin[d], N * sizeof(double));
@@ -952,7 +1020,13 @@ int ora_get(const ora_state* s, int32_t which, int32_t corr, double* dst) {
                 memcpy(dst + c * N, s->rho_p[c], N * sizeof(double));
             return ORA_OK;
         case ORA_P:
-            for (size_t P = 0; P < N; ++P) dst[P] = s->p.C * pow(s->rho[P], s->p.gamma);
+            for (size_t P = 0; P < N; ++P)
+                dst[P] = s->p.closure == ORA_FOURIER ? s->rho[P] * s->p.R_gas * s->T[P]
+                                                     : s->p.C * pow(s->rho[P], s->p.gamma);
+            return ORA_OK;
+        case ORA_T:
+            if (s->p.closure != ORA_FOURIER) return ORA_ERR_INVALID;
+            memcpy(dst, s->T, N * sizeof(double));
             return ORA_OK;
         default: break;
     }
@@ -1017,7 +1091,15 @@ int ora_stats(const ora_state* s, double* out) {
         for (int d = 0; d < 3; ++d) q += s->u[d][P] * s->u[d][P];
         t[P] = q;
     }
-    double c0 = sqrt(s->p.gamma * s->p.C * pow(rmean, s->p.gamma - 1.0));
+    /* sound speed of the mean state: barotropic gamma C <rho>^(gamma-1); Fourier
+     * (ideal gas) gamma' R <T> with gamma' = c_p/c_v = 1 + R/c_v */
+    double c0;
+    if (s->p.closure == ORA_FOURIER) {
+        double tm = sum_field(n, s->T) * invN;
+        c0 = sqrt((1.0 + s->p.R_gas / s->p.cv) * s->p.R_gas * tm);
+    } else {
+        c0 = sqrt(s->p.gamma * s->p.C * pow(rmean, s->p.gamma - 1.0));
+    }
     out[ORA_STAT_MACH_RMS] = sqrt(sum_field(n, t) * invN) / c0;
     out[ORA_STAT_MASS_GAS] = rmean * (double)N * s->V;
     for (int c = 0; c < s->p.n_classes; ++c) {

@@ -65,7 +65,16 @@ typedef struct {
     /* gravity: the dust settles with u_j = u + tau_j (g - Du/Dt); with two_way
      * the mixture also feels its buoyancy */
     double gravity[3];
+    /* closure: 0 barotropic p = C rho^gamma; 1 Fourier: ideal gas p = rho R T
+     * with an energy equation whose heat flux is q = -kappa grad T (c_v: heat
+     * capacity at constant volume per unit mass; T0: initial uniform
+     * temperature, see ora_set_temperature) */
+    int32_t closure;
+    double R_gas, cv, kappa, T0;
 } ora_params;
+
+#define ORA_BAROTROPIC 0
+#define ORA_FOURIER 1
 
 typedef struct {
     double t, dt, courant;
@@ -93,7 +102,8 @@ enum {
     ORA_U = 1,        /* 3 n^3 */
     ORA_PHI = 2,      /* 3 n^3 faces */
     ORA_RHO_P = 3,    /* n_classes n^3 */
-    ORA_P = 4,        /* n^3: C rho^gamma */
+    ORA_P = 4,        /* n^3: C rho^gamma (Fourier: rho R T) */
+    ORA_T = 5,        /* n^3: temperature (Fourier closure) */
     /* pressure system of corrector `corr` of the last step */
     ORA_SYS_B = 10,   /* right-hand side b */
     ORA_SYS_W = 11,   /* rho/a_P at cell centres (face coefficient source) */
@@ -117,6 +127,8 @@ double ora_time(const ora_state* s);
 void ora_destroy(ora_state* s);
 /* keep copies of each corrector's pressure system (b, w, psi/dt, K, p', p0, diag) */
 void ora_set_capture(ora_state* s, int32_t on);
+/* Fourier closure: the temperature field (n^3) before the first step. */
+int ora_set_temperature(ora_state* s, const double* T);
 int ora_num_threads(void);
 
 /* ---- operators (exposed for the pins) ---- */
