@@ -142,7 +142,24 @@ typedef struct {
                                   dusty gas, third footnote) */
     double gravity[3];         /* g: the dust settles with u_j = u + tau_j (g - Du/Dt); with
                                   two_way the mixture also feels its buoyancy */
+    int32_t closure;           /* PISOC_BAROTROPIC (p = C rho^gamma, the step above) or
+                                  PISOC_FOURIER (Results, first footnote): the ideal gas
+                                  p = rho R_gas T with an energy equation whose heat flux
+                                  is q = -kappa grad T.  After the momentum predictor, the
+                                  internal energy c_v T is predicted like the momentum
+                                  (backward Euler, I4 convection with phi^n, compact
+                                  Laplacian for q, n_mom_sweeps Jacobi sweeps from T^n),
+                                  with the compression work -p^n div u^n; the correctors
+                                  take p0 = rho_k R T* and psi = 1/(R T*), and T* is
+                                  T^{n+1}.  FOURIER needs FP64, one grid (no ensemble)
+                                  and two_way = 0; C and gamma are then unused */
+    double R_gas, cv, kappa;   /* FOURIER: gas constant, c_v, heat conductivity (> 0,
+                                  > 0, >= 0) */
+    double T0;                 /* FOURIER: initial uniform temperature (> 0); see
+                                  pisoc_set_temperature */
 } pisoc_params;
+
+enum { PISOC_BAROTROPIC = 0, PISOC_FOURIER = 1 };
 
 typedef struct {
     double t, dt, courant;           /* time after the step, dt, sigma*dt */
@@ -173,7 +190,7 @@ enum {
     PISOC_FIELD_U = 1u << 1,        /* 3 n^3 */
     PISOC_FIELD_PHI = 1u << 2,      /* 3 n^3 face mass fluxes */
     PISOC_FIELD_RHO_P = 1u << 3,    /* n_classes n^3 */
-    PISOC_FIELD_P = 1u << 4,        /* n^3, C rho^gamma */
+    PISOC_FIELD_P = 1u << 4,        /* n^3, C rho^gamma (PISOC_FOURIER: rho R_gas T) */
     PISOC_FIELD_PSOLVE_B = 1u << 5, /* captured: right-hand side b (needs capture) */
     PISOC_FIELD_PSOLVE_X = 1u << 6, /* captured: solution p' */
     PISOC_FIELD_P_PREV = 1u << 7,   /* captured: p(rho) at the corrector's start */
@@ -186,8 +203,9 @@ enum {
     PISOC_FIELD_PSOLVE_W = 1u << 12,/* captured: w = rho/a_P, whose I4 face values are the
                                        operator's K_f (with diag, M is then known:
                                        psi/dt = diag - (1/h^2) sum_f K_f) */
-    PISOC_FIELD_PSOLVE_PSIDT = 1u << 13 /* captured: that psi/dt, formed from the captured
+    PISOC_FIELD_PSOLVE_PSIDT = 1u << 13,/* captured: that psi/dt, formed from the captured
                                            diag and w (for pisoc_helm_solve) */
+    PISOC_FIELD_T = 1u << 14        /* n^3, temperature (PISOC_FOURIER only) */
 };
 
 /* Bytes of device workspace pisoc_init needs for these parameters (0 if the
@@ -227,6 +245,11 @@ pisoc_status pisoc_step(pisoc_ctx* ctx, int32_t n_steps, pisoc_step_info* h_info
  * destination per set bit of `which`, in increasing bit order (d_dst[0] for
  * the lowest set bit), each sized as its selector states.  Asynchronous. */
 pisoc_status pisoc_fields(pisoc_ctx* ctx, uint32_t which, double* const* d_dst);
+
+/* PISOC_FOURIER: replace the temperature field of the current state (n^3 FP64
+ * device array, > 0) -- e.g. a non-uniform initial temperature before the
+ * first step.  PISOC_ERR_INVALID for the barotropic closure.  Synchronises. */
+pisoc_status pisoc_set_temperature(pisoc_ctx* ctx, const double* d_T);
 
 /* Volume statistics of the current state (FP64 reductions; synchronises). */
 pisoc_status pisoc_get_stats(pisoc_ctx* ctx, pisoc_stats* h_out);

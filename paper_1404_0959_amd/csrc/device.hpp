@@ -29,7 +29,18 @@ struct Phys {
     double h, inv_h, inv_h2, V, inv_V, A;
     double gamma, C, mu;
     double g[3];        // gravity (settling drift; with two-way coupling also buoyancy)
+    // Fourier closure (FP64 single grids): p = rho R T with the energy
+    // equation; tn: T^n, ts: T* of the current step (set before each step)
+    int fourier;
+    double R, cv, kappa;
+    const double* tn;
+    const double* ts;
 };
+
+// The compressibility factor of the corrector: psi = rho / (gamma_psi p) with
+// gamma_psi = gamma for the barotropic closure (d rho / d p of C rho^gamma)
+// and 1 for the ideal gas at the predicted temperature (1 / (R T)).
+__host__ __device__ inline double gamma_psi(const Phys& ph) { return ph.fourier ? 1.0 : ph.gamma; }
 
 // State of one pressure solve, kept on the device so that CG never returns to
 // the host between iterations.

@@ -61,10 +61,20 @@ __global__ void k_cast_out(const T* __restrict__ src, double* __restrict__ dst, 
 // p = p_ref + p_dev(r) as FP64 (one member)
 template <typename T>
 __global__ void k_pressure_out(double gamma, double rho_ref, double p_ref, const T* __restrict__ r,
-                               double* __restrict__ dst, size_t count) {
+                               double* __restrict__ dst, size_t count, const double* temp,
+                               double R) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < count; i += stride) dst[i] = p_ref + pdev((double)r[i], rho_ref, p_ref, gamma);
+    for (; i < count; i += stride)
+        dst[i] = temp ? (rho_ref + (double)r[i]) * R * temp[i]
+                      : p_ref + pdev((double)r[i], rho_ref, p_ref, gamma);
+}
+
+// dst[i] = v (FP64 fill).
+__global__ void k_fill(double* __restrict__ dst, size_t count, double v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) dst[i] = v;
 }
 
 // Initial face mass fluxes phi_d = I4(rho) I4(u_d) A.
@@ -207,6 +217,8 @@ __global__ void __launch_bounds__(kBlock) k_predict(Phys ph, DevState* st, const
     T r, a, dv, p;
     predict_cell(fp, fm, ul, rnP, dt, inv_V, inv_h, diag_visc, (T)(st + mem_)->rho_ref,
                  (st + mem_)->p_ref, ph.gamma, r, a, dv, p);
+    if (ph.fourier)   // ideal gas at T^n
+        p = (T)(((st + mem_)->rho_ref + (double)rnP) * ph.R * ph.tn[P] - (st + mem_)->p_ref);
     rs[P] = r;
     aP[P] = a;
     divu[P] = dv;
@@ -345,7 +357,9 @@ __global__ void __launch_bounds__(kBlock) k_mom_sweep(Phys ph, const DevState* s
     for (int m = 0; m < 3; ++m) uout[m * N + P] = out[m];
     if (HBYA) {
         w[P] = ((T)(st + mem_)->rho_ref + rkP) * ia;
-        p0[P] = pdev(rkP, (st + mem_)->rho_ref, (st + mem_)->p_ref, ph.gamma);
+        p0[P] = ph.fourier   // ideal gas at the predicted temperature T*
+                    ? (T)(((st + mem_)->rho_ref + (double)rkP) * ph.R * ph.ts[P] - (st + mem_)->p_ref)
+                    : pdev(rkP, (st + mem_)->rho_ref, (st + mem_)->p_ref, ph.gamma);
     }
     END_CELLS
 }
@@ -652,7 +666,7 @@ __global__ void __launch_bounds__(kBlock) k_corr_rhs(
     loads_issued();
     double b;
     T dgT, phf[3];
-    corr_rhs_cell(wv, rv, hl, pv, rnP, dt, rref, pref, ph.gamma, ph.A, ph.inv_V, ph.inv_h,
+    corr_rhs_cell(wv, rv, hl, pv, rnP, dt, rref, pref, gamma_psi(ph), ph.A, ph.inv_V, ph.inv_h,
                   ph.inv_h2, b, dgT, phf);
     corr_rhs_store(P, N, b, dgT, phf, pref + (double)pv[0], phiH, rvec, diag, snap_b, snap_diag,
                    snap_p0, b64, v);
@@ -806,7 +820,7 @@ __global__ void __launch_bounds__(kTX * kTY, sizeof(T) == 4 ? 4 : 2) k_corr_rhs_
         lds_barrier();
         double b;
         T dgT, phf[3];
-        corr_rhs_cell(wv, rv, hl, pv, cn, dt, rref, pref, ph.gamma, ph.A, ph.inv_V, ph.inv_h,
+        corr_rhs_cell(wv, rv, hl, pv, cn, dt, rref, pref, gamma_psi(ph), ph.A, ph.inv_V, ph.inv_h,
                       ph.inv_h2, b, dgT, phf);
         corr_rhs_store(P, N, b, dgT, phf, pref + (double)pv[0], phiH, rvec, diag, snap_b,
                        snap_diag, snap_p0, b64, v);
@@ -1667,6 +1681,67 @@ __global__ void __launch_bounds__(kBlock) k_psidt_of(int n, double inv_h2,
         for (int d = 0; d < 3; ++d) sumK += i4(w, c, d, 0) + i4(w, c, d, -1);
         out[i] = diag[i] - sumK * inv_h2;
     }
+}
+
+// ---- Fourier closure: the energy predictor (gathered; FP64 runs only) ----
+// The internal energy c_v T of the gas, discretised like the momentum
+// predictor (backward Euler, I4 convection with the old fluxes split into the
+// diagonal (9/16) div(phi) and the rest, compact Laplacian for the heat flux
+// q = -kappa grad T), with the compression work -p^n div u^n:
+//   a_T T_P + N(T)_P = s_T,
+//   a_T = c_v (rho*/dt + (9/16) div phi) + 6 kappa / h^2,
+//   N(T) = c_v [div(phi I4(T)) - (9/16) div(phi) T_P] - (kappa / h^2) sum_nb T_nb,
+//   s_T = c_v rho^n T^n / dt - p^n div u^n,
+// solved by Jacobi sweeps from T^n (the momentum predictor's count).
+template <typename T>
+__device__ inline double div_phi_at(const T* __restrict__ phi, const CellIdx& c, size_t N, double inv_V) {
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s += (double)phi[d * N + c.self()] - (double)phi[d * N + c.sh(d, -1)];
+    return s * inv_V;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_energy_setup(Phys ph, const DevState* st,
+                                                         const T* __restrict__ rn,
+                                                         const T* __restrict__ rs,
+                                                         const T* __restrict__ phi,
+                                                         const T* __restrict__ divu,
+                                                         const T* __restrict__ pn,
+                                                         double* __restrict__ aT,
+                                                         double* __restrict__ sT) {
+    MEMBER(ph)
+    const size_t N = ncell(ph);
+    const double dt = (st + mem_)->dt, rref = (st + mem_)->rho_ref, pref = (st + mem_)->p_ref;
+    const double diag_k = 6.0 * ph.kappa * ph.inv_h2;
+    FOR_CELLS(ph)
+    const double dphi = div_phi_at(phi, c, N, ph.inv_V);
+    aT[P] = ph.cv * ((rref + (double)rs[P]) / dt + 0.5625 * dphi) + diag_k;
+    sT[P] = ph.cv * (rref + (double)rn[P]) * ph.tn[P] / dt - (pref + (double)pn[P]) * (double)divu[P];
+    END_CELLS
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_energy_sweep(Phys ph, const DevState* st,
+                                                         const double* __restrict__ tin,
+                                                         double* __restrict__ tout,
+                                                         const T* __restrict__ phi,
+                                                         const double* __restrict__ aT,
+                                                         const double* __restrict__ sT) {
+    MEMBER(ph)
+    const size_t N = ncell(ph);
+    FOR_CELLS(ph)
+    double conv = 0.0, nb = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        conv += (double)phi[d * N + P] * i4(tin, c, d, 0) -
+                (double)phi[d * N + c.sh(d, -1)] * i4(tin, c, d, -1);
+        nb += tin[c.sh(d, 1)] + tin[c.sh(d, -1)];
+    }
+    const double dphi = div_phi_at(phi, c, N, ph.inv_V);
+    const double off = ph.cv * (conv * ph.inv_V - 0.5625 * dphi * tin[P]) - ph.kappa * ph.inv_h2 * nb;
+    tout[P] = (sT[P] - off) / aT[P];
+    END_CELLS
 }
 
 // y = M x for the stand-alone operator entry point (psi/dt given as a field).
@@ -3160,9 +3235,9 @@ void Ops<T>::cast_out(hipStream_t s, const T* src, double* dst, size_t count, do
 }
 template <typename T>
 void Ops<T>::pressure_out(hipStream_t s, const Phys& ph, double rho_ref, double p_ref, const T* r,
-                          double* dst) {
+                          double* dst, const double* temp) {
     hipLaunchKernelGGL(k_pressure_out<T>, lin_grid(ph.N), dim3(kBlock), 0, s, ph.gamma, rho_ref,
-                       p_ref, r, dst, ph.N);
+                       p_ref, r, dst, ph.N, temp, ph.R);
 }
 template <typename T>
 void Ops<T>::init_phi(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
@@ -3328,6 +3403,21 @@ template <typename T>
 void Ops<T>::helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt, const T* w,
                         const T* x, T* y) {
     LAUNCH(k_helm_apply<T>, L, s, ph, psidt, w, x, y);
+}
+template <typename T>
+void Ops<T>::energy_setup(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                          const T* rn, const T* rs, const T* phi, const T* divu, const T* pn,
+                          double* aT, double* sT) {
+    LAUNCH(k_energy_setup<T>, L, s, ph, st, rn, rs, phi, divu, pn, aT, sT);
+}
+template <typename T>
+void Ops<T>::energy_sweep(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                          const double* tin, double* tout, const T* phi, const double* aT,
+                          const double* sT) {
+    LAUNCH(k_energy_sweep<T>, L, s, ph, st, tin, tout, phi, aT, sT);
+}
+void fill_value(hipStream_t s, double* dst, size_t count, double v) {
+    hipLaunchKernelGGL(k_fill, lin_grid(count), dim3(kBlock), 0, s, dst, count, v);
 }
 template <typename T>
 void Ops<T>::cheb_theta(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt, const T* diag,

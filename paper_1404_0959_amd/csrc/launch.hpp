@@ -52,6 +52,9 @@ constexpr int kSmallTX = 16;
 constexpr int kRowCells = 4, kRowWaves = 8, kRowBlocks = 256;
 Launch make_spmv_launch(int n, int batch, int elem_bytes, int cz_tile = 0);
 
+// dst[0..count) = v (FP64).
+void fill_value(hipStream_t s, double* dst, size_t count, double v);
+
 // psi/dt = diag - (1/h^2) sum_f I4(w)_f of a captured pressure system (n^3 FP64).
 void psidt_of(hipStream_t s, int n, const double* diag, const double* w, double* out);
 
@@ -105,8 +108,9 @@ struct Ops {
     static void cast_in(hipStream_t s, const double* src, T* dst, size_t count, double shift);
     static void cast_out(hipStream_t s, const T* src, double* dst, size_t count, double shift);
     // one member's pressure p_ref + p_dev(r) (r points at the member's cells)
+    // p = C rho^gamma, or rho R T with temp non-null (Fourier closure)
     static void pressure_out(hipStream_t s, const Phys& ph, double rho_ref, double p_ref,
-                             const T* r, double* dst);
+                             const T* r, double* dst, const double* temp = nullptr);
     static void init_phi(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                          const T* r, const T* u, T* phi);
     static void cfl(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
@@ -149,6 +153,13 @@ struct Ops {
                          DevState* st, int k, const CgArgs<T>& a);
     static void helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt,
                            const T* w, const T* x, T* y);
+    // Fourier closure: the energy predictor's coefficients and one Jacobi sweep
+    static void energy_setup(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                             const T* rn, const T* rs, const T* phi, const T* divu, const T* pn,
+                             double* aT, double* sT);
+    static void energy_sweep(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
+                             const double* tin, double* tout, const T* phi, const double* aT,
+                             const double* sT);
     // CG preconditioned by a Chebyshev polynomial (stand-alone solve): the
     // interval's lower end, then per iteration the residual/preconditioner and
     // the direction/operator launches

@@ -73,6 +73,7 @@ struct Layout {
     size_t b64, x64a, x64b, xf;  // FP64 refinement fields, FP32 solution copy (FP32 storage only)
     size_t wpk, nx4, na, nb, ny, bsave;  // learned guess: packed weights, activations
     size_t xprev;  // previous-step guess: each corrector's last solution
+    size_t t0, t1, tw, eaT, esT;  // Fourier closure: T (two rotating), sweep scratch, a_T, s_T
     size_t total;
     unsigned max_blocks;     // column length of the partials (all members)
 };
@@ -182,6 +183,13 @@ bool valid_params(const pisoc_params* p, std::string* why) {
     if (p->guess_audit < 0) return fail("guess_audit must be >= 0");
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(p->gravity[d])) return fail("gravity must be finite");
+    if (p->closure != PISOC_BAROTROPIC && p->closure != PISOC_FOURIER) return fail("unknown closure");
+    if (p->closure == PISOC_FOURIER) {
+        if (!(p->R_gas > 0.0) || !(p->cv > 0.0) || !(p->kappa >= 0.0) || !(p->T0 > 0.0))
+            return fail("Fourier closure needs R_gas > 0, cv > 0, kappa >= 0 and T0 > 0");
+        if (p->precision != PISOC_FP64) return fail("Fourier closure needs FP64");
+        if (p->two_way) return fail("Fourier closure with two_way is not supported");
+    }
     return true;
 }
 
@@ -217,6 +225,13 @@ Layout make_layout(const pisoc_params* p, int batch) {
     }
     L.snap = p->capture ? take((p->guess != PISOC_GUESS_ZERO ? 10 : 8) * sizeof(double) * N)
                         : 0;
+    if (p->closure == PISOC_FOURIER) {   // FP64 only
+        L.t0 = take(sizeof(double) * N);
+        L.t1 = take(sizeof(double) * N);
+        L.tw = take(sizeof(double) * N);
+        L.eaT = take(sizeof(double) * N);
+        L.esT = take(sizeof(double) * N);
+    }
     if (p->guess == PISOC_GUESS_PREVIOUS) {
         // each corrector's solution of the last step, and the saved b of a fallback
         L.xprev = take(es * N * (size_t)p->n_corr);
@@ -269,6 +284,7 @@ struct pisoc_ctx {
     int ucur_slot;  // u_idx slot holding u* after the predictor sweeps (1 or 2)
     size_t rn, rk, phin, phik, rhop, rhop1;
     size_t fdn, fdk;   // two-way coupling: dust mass fluxes of the last step / this one
+    size_t tn, tk;     // Fourier closure: T^n / T* of the step being enqueued
     double t;
     int64_t steps;
     int pred_first[PISOC_MAX_CORR];  // CG iterations of the last first solve (all members)
@@ -368,6 +384,10 @@ Phys make_phys(const pisoc_params* p, const Launch& L, int batch) {
     ph.C = p->C;
     ph.mu = p->mu;
     for (int d = 0; d < 3; ++d) ph.g[d] = p->gravity[d];
+    ph.fourier = p->closure == PISOC_FOURIER ? 1 : 0;
+    ph.R = p->R_gas;
+    ph.cv = p->cv;
+    ph.kappa = p->kappa;
     return ph;
 }
 
@@ -630,6 +650,20 @@ void enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
     if (S.snap)   // the predictor's output u*
         for (int d = 0; d < 3; ++d)
             O::cast_out(s, uin + d * ctx->NT(), S.snap + (5 + d) * ctx->NT(), ctx->NT(), 0.0);
+    if (ph.fourier) {
+        // energy predictor: T* in tk after the sweeps (ping-pong with tw)
+        double* aT = ctx->f<double>(ctx->lay.eaT);
+        double* sT = ctx->f<double>(ctx->lay.esT);
+        double* tk = ctx->f<double>(ctx->tk);
+        double* tw = ctx->f<double>(ctx->lay.tw);
+        O::energy_setup(L, s, ph, st, S.rn, S.rk, S.phin, S.divu, S.pn, aT, sT);
+        const double* tin = ph.tn;
+        for (int i = 0; i < p.n_mom_sweeps; ++i) {
+            double* tout = ((p.n_mom_sweeps - 1 - i) & 1) ? tw : tk;
+            O::energy_sweep(L, s, ph, st, tin, tout, S.phin, aT, sT);
+            tin = tout;
+        }
+    }
 }
 
 template <typename T>
@@ -968,6 +1002,10 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
     const bool cfl_ready = eager && ctx->cfl_ready;
     ctx->cfl_ready = false;
     ctx->nb_cfl_next = 0;
+    if (ctx->ph.fourier) {   // this step's temperature buffers
+        ctx->ph.tn = ctx->f<double>(ctx->tn);
+        ctx->ph.ts = ctx->f<double>(ctx->tk);
+    }
     enqueue_front<T>(ctx, S, cfl_ready);
     // with the audit on, an eager step takes this step's decision and a
     // captured one the verdict it was built with (audit_decide_capture)
@@ -1029,6 +1067,7 @@ void rotate(pisoc_ctx* ctx) {
     // two-way with dust: this step's F_d becomes the next step's (without dust
     // both stay zero)
     if (ctx->prm.two_way && ctx->prm.n_classes > 0) std::swap(ctx->fdn, ctx->fdk);
+    if (ctx->prm.closure == PISOC_FOURIER) std::swap(ctx->tn, ctx->tk);
 }
 
 // Step record of member m from its device state.
@@ -1147,6 +1186,9 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     ctx->TS = make_spmv_launch(prm->n, batch, prm->precision == PISOC_FP64 ? 8 : 4);
     // PISOC_UNTILED=1 selects the untiled kernels (kernel-comparison tests)
     if (const char* e = std::getenv("PISOC_UNTILED"); e && e[0] == '1') ctx->TL = ctx->TS = Launch{};
+    // the Fourier closure runs the gathered field kernels (the tiled z-marches
+    // evaluate the barotropic closure inline); the CG kernel is closure-free
+    if (prm->closure == PISOC_FOURIER) ctx->TL = Launch{};
     ctx->L = make_launch(prm->n, batch);
     ctx->ph = make_phys(prm, ctx->L, batch);
     ctx->st = reinterpret_cast<DevState*>(ctx->ws + lay.state);
@@ -1247,7 +1289,8 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
             return PISOC_ERR_INVALID;
         }
         ctx->rho_ref[m] = rr;
-        ctx->p_ref[m] = mprm[m].C * std::pow(rr, prm->gamma);
+        ctx->p_ref[m] = prm->closure == PISOC_FOURIER ? rr * prm->R_gas * prm->T0
+                                                      : mprm[m].C * std::pow(rr, prm->gamma);
     }
     for (int m = 0; m < batch; ++m) {
         DevState init{};
@@ -1290,6 +1333,11 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     };
     if (prm->precision == PISOC_FP64) convert(double{});
     else convert(float{});
+    if (prm->closure == PISOC_FOURIER) {
+        ctx->tn = lay.t0;
+        ctx->tk = lay.t1;
+        fill_value(s, ctx->f<double>(ctx->tn), NT, prm->T0);
+    }
     if (prm->guess == PISOC_GUESS_LEARNED)
         net_pack_forward(s, reinterpret_cast<const float*>(prm->d_guess_weights), ctx->ws + lay.wpk);
     return sync_state(ctx);
@@ -1338,10 +1386,20 @@ pisoc_status member_fields(pisoc_ctx* ctx, int m, uint32_t which, double* const*
             case PISOC_FIELD_P:
                 if (f64)
                     Ops<double>::pressure_out(s, ctx->ph, ctx->rho_ref[m], ctx->p_ref[m],
-                                              ctx->f<double>(ctx->rn) + off, dst);
+                                              ctx->f<double>(ctx->rn) + off, dst,
+                                              ctx->ph.fourier ? ctx->f<double>(ctx->tn) + off
+                                                              : nullptr);
                 else
                     Ops<float>::pressure_out(s, ctx->ph, ctx->rho_ref[m], ctx->p_ref[m],
                                              ctx->f<float>(ctx->rn) + off, dst);
+                break;
+            case PISOC_FIELD_T:
+                if (!ctx->ph.fourier) {
+                    ctx->err = "temperature requested without the Fourier closure";
+                    return PISOC_ERR_INVALID;
+                }
+                HIP_TRY(ctx, hipMemcpyAsync(dst, ctx->f<double>(ctx->tn) + off, N * sizeof(double),
+                                            hipMemcpyDeviceToDevice, s));
                 break;
             case PISOC_FIELD_PSOLVE_PSIDT:
                 if (!snap) {
@@ -1411,6 +1469,11 @@ pisoc_status all_stats(pisoc_ctx* ctx, pisoc_stats* out) {
     set_affine(s, ctx->st, B, 0, N);
     if (f64) affine(double{}, ctx->rn, 0); else affine(float{}, ctx->rn, 0);
     finalize_sums(s, ctx->part(PS_STAT), nb, B, 2, ctx->st, 4);
+    if (ph.fourier) {   // sum T into red[6]
+        Ops<double>::sum_affine_sq(ctx->L, s, ph, nullptr, ctx->f<double>(ctx->tn), 0.0, 0.0,
+                                   ctx->part(PS_STAT));
+        finalize_sums(s, ctx->part(PS_STAT), nb, B, 2, ctx->st, 5);
+    }
     pisoc_status st = sync_state(ctx);
     if (st != PISOC_OK) return st;
     for (int m = 0; m < B; ++m) {
@@ -1422,7 +1485,11 @@ pisoc_status all_stats(pisoc_ctx* ctx, pisoc_stats* out) {
         o.ke = h.red[0] / N;
         o.enstrophy = h.red[1] / N;
         o.rho_rms = std::sqrt(h.red[4] / N) / rmean;
-        o.mach_rms = std::sqrt(h.red[2] / N) / std::sqrt(ph.gamma * C * std::pow(rmean, ph.gamma - 1.0));
+        // sound speed of the mean state: gamma C <rho>^(gamma-1), or for the
+        // ideal gas (1 + R/c_v) R <T>
+        const double c0sq = ph.fourier ? (1.0 + ph.R / ph.cv) * ph.R * (h.red[6] / N)
+                                       : ph.gamma * C * std::pow(rmean, ph.gamma - 1.0);
+        o.mach_rms = std::sqrt(h.red[2] / N) / std::sqrt(c0sq);
         o.mass_gas = rmean * N * ph.V;
     }
     const size_t NT = ctx->NT();
@@ -1864,6 +1931,10 @@ bool ens_classes(const pisoc_params* members, int32_t count, std::vector<std::ve
     }
     for (int m = 0; m < count; ++m) {
         if (!valid_params(&members[m], why)) return false;
+        if (members[m].closure != PISOC_BAROTROPIC) {
+            if (why) *why = "ensembles take the barotropic closure only";
+            return false;
+        }
         if (!same_class_params(members[m], members[0])) {
             if (why) *why = "members may differ only in n, C and tau_p";
             return false;
@@ -1966,6 +2037,18 @@ pisoc_status pisoc_step(pisoc_ctx* ctx, int32_t n_steps, pisoc_step_info* h_info
 pisoc_status pisoc_fields(pisoc_ctx* ctx, uint32_t which, double* const* d_dst) {
     if (!ctx || !d_dst) return PISOC_ERR_INVALID;
     return member_fields(ctx, 0, which, d_dst);
+}
+
+pisoc_status pisoc_set_temperature(pisoc_ctx* ctx, const double* d_T) {
+    if (!ctx || !d_T) return PISOC_ERR_INVALID;
+    if (!ctx->ph.fourier) {
+        ctx->err = "pisoc_set_temperature needs the Fourier closure";
+        return PISOC_ERR_INVALID;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->f<double>(ctx->tn), d_T, ctx->N() * sizeof(double),
+                                hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return PISOC_OK;
 }
 
 pisoc_status pisoc_get_stats(pisoc_ctx* ctx, pisoc_stats* out) {

@@ -27,13 +27,14 @@ FLAG_DUST_NEG, FLAG_DUST_NONFINITE, FLAG_DUST_DIAG, FLAG_DUST_COURANT = 64, 128,
 FIELD_RHO, FIELD_U, FIELD_PHI, FIELD_RHO_P, FIELD_P = 1, 2, 4, 8, 16
 FIELD_PSOLVE_B, FIELD_PSOLVE_X, FIELD_P_PREV, FIELD_PSOLVE_DIAG = 32, 64, 128, 256
 FIELD_USTAR, FIELD_GUESS, FIELD_GUESS_X0, FIELD_PSOLVE_W = 512, 1024, 2048, 4096
-FIELD_PSOLVE_PSIDT = 8192
+FIELD_PSOLVE_PSIDT, FIELD_T = 8192, 16384
+BAROTROPIC, FOURIER = 0, 1
 
 EXPORTED = [
     "pisoc_workspace_bytes", "pisoc_init", "pisoc_step", "pisoc_fields", "pisoc_get_stats",
     "pisoc_time", "pisoc_steps_done", "pisoc_destroy", "pisoc_last_error", "pisoc_status_string",
     "pisoc_helm_apply", "pisoc_helm_workspace_bytes", "pisoc_helm_solve",
-    "pisoc_helm_solve_precond",
+    "pisoc_helm_solve_precond", "pisoc_set_temperature",
     "pisoc_helm_solve_noalloc",
     "pisoc_profile", "pisoc_profile_read",
     "pisoc_net_workspace_bytes", "pisoc_net_forward", "pisoc_net_grad", "pisoc_net_adam",
@@ -66,6 +67,8 @@ class Params(C.Structure):
         ("inner_tol", C.c_double), ("max_refine", C.c_int32),
         ("capture", C.c_int32), ("guess_audit", C.c_int32),
         ("two_way", C.c_int32), ("gravity", C.c_double * 3),
+        ("closure", C.c_int32), ("R_gas", C.c_double), ("cv", C.c_double),
+        ("kappa", C.c_double), ("T0", C.c_double),
     ]
 
 
@@ -142,6 +145,8 @@ def lib():
     L.pisoc_helm_solve_precond.argtypes = [i32, vp, vp, vp, vp, f64, i32, i32, vp, sz, vp,
                                            C.POINTER(i32), C.POINTER(f64)]
     L.pisoc_helm_solve_precond.restype = C.c_int
+    L.pisoc_set_temperature.argtypes = [vp, vp]
+    L.pisoc_set_temperature.restype = C.c_int
     L.pisoc_helm_solve_noalloc.argtypes = [i32, vp, vp, vp, vp, f64, i32, vp,
                                            C.POINTER(i32), C.POINTER(f64)]
     L.pisoc_helm_solve_noalloc.restype = C.c_int
@@ -226,7 +231,9 @@ def make_params(n, *, gamma, C_, mu, tau_p=(), cfl=0.5, dt_growth=1.2, dt_fixed=
                 n_corr=2, n_mom_sweeps=4, n_dust_sweeps=4, p_tol=1e-8, p_maxit=500,
                 precision=FP64, guess=GUESS_ZERO, guess_weights=None, inner_tol=1e-7,
                 max_refine=20, capture=False, guess_audit=0, two_way=False,
-                gravity=(0.0, 0.0, 0.0)) -> Params:
+                gravity=(0.0, 0.0, 0.0), fourier=None) -> Params:
+    """fourier: None (barotropic) or dict(R=, cv=, kappa=, T0=) for the ideal gas
+    with the energy equation."""
     p = Params()
     p.n = n
     p.n_classes = len(tau_p)
@@ -244,13 +251,16 @@ def make_params(n, *, gamma, C_, mu, tau_p=(), cfl=0.5, dt_growth=1.2, dt_fixed=
     p.two_way = 1 if two_way else 0
     for d in range(3):
         p.gravity[d] = gravity[d]
+    if fourier is not None:
+        p.closure = FOURIER
+        p.R_gas, p.cv, p.kappa, p.T0 = fourier["R"], fourier["cv"], fourier["kappa"], fourier["T0"]
     return p
 
 
 class Solver:
     """One simulation on one GPU, bound to a workspace tensor and a stream."""
 
-    def __init__(self, n, rho, u, rho_p=None, *, device="cuda:0", stream=None, **kw):
+    def __init__(self, n, rho, u, rho_p=None, *, device="cuda:0", stream=None, T=None, **kw):
         torch = _torch()
         self.torch = torch
         self.device = torch.device(device)
@@ -279,6 +289,11 @@ class Solver:
         if st != OK:
             raise PisocError(st, "pisoc_init failed")
         self._h = h
+        if T is not None:
+            t_d = torch.as_tensor(T, dtype=torch.float64, device=dev).contiguous()
+            st = L.pisoc_set_temperature(h, t_d.data_ptr())
+            if st != OK:
+                raise PisocError(st, self.last_error())
 
     @classmethod
     def from_case(cls, case, **kw):
@@ -316,7 +331,8 @@ class Solver:
                   FIELD_PSOLVE_B: (n, n, n), FIELD_PSOLVE_X: (n, n, n),
                   FIELD_P_PREV: (n, n, n), FIELD_PSOLVE_DIAG: (n, n, n),
                   FIELD_USTAR: (3, n, n, n), FIELD_GUESS: (n, n, n), FIELD_GUESS_X0: (n, n, n),
-                  FIELD_PSOLVE_W: (n, n, n), FIELD_PSOLVE_PSIDT: (n, n, n)}
+                  FIELD_PSOLVE_W: (n, n, n), FIELD_PSOLVE_PSIDT: (n, n, n),
+                  FIELD_T: (n, n, n)}
         bits = [b for b in sorted(shapes) if which & b]
         outs = [torch.empty(shapes[b], dtype=torch.float64, device=self.device) for b in bits]
         arr = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
@@ -459,7 +475,8 @@ class Ensemble:
                   FIELD_PSOLVE_B: (n, n, n), FIELD_PSOLVE_X: (n, n, n),
                   FIELD_P_PREV: (n, n, n), FIELD_PSOLVE_DIAG: (n, n, n),
                   FIELD_USTAR: (3, n, n, n), FIELD_GUESS: (n, n, n), FIELD_GUESS_X0: (n, n, n),
-                  FIELD_PSOLVE_W: (n, n, n), FIELD_PSOLVE_PSIDT: (n, n, n)}
+                  FIELD_PSOLVE_W: (n, n, n), FIELD_PSOLVE_PSIDT: (n, n, n),
+                  FIELD_T: (n, n, n)}
         bits = [b for b in sorted(shapes) if which & b]
         outs = [torch.empty(shapes[b], dtype=torch.float64, device=self.device) for b in bits]
         arr = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])

@@ -67,6 +67,34 @@ def test_invalid_params_rejected(lib, field, value):
     assert st == P.ERR_INVALID and not h.value
 
 
+FOURIER = dict(R=1.0, cv=2.5, kappa=1e-3, T0=50.0)
+
+
+@pytest.mark.parametrize("change", [
+    dict(closure=2), dict(R_gas=0.0), dict(cv=-1.0), dict(kappa=-1e-3), dict(T0=0.0),
+    dict(precision=P.FP32_REFINED, inner_tol=1e-6), dict(two_way=1),
+])
+def test_fourier_params_rejected(lib, change):
+    """The Fourier closure's constants must be positive (kappa >= 0); it runs in
+    FP64 without two-way coupling."""
+    p = P.make_params(32, gamma=1.4, C_=53.6, mu=1e-3, tau_p=(0.01,), fourier=FOURIER)
+    assert lib.pisoc_workspace_bytes(ctypes.byref(p)) > 0
+    for k, v in change.items():
+        setattr(p, k, v)
+    assert lib.pisoc_workspace_bytes(ctypes.byref(p)) == 0
+
+
+def test_fourier_workspace_and_ensemble_rejection(lib):
+    """The closure adds five FP64 cell fields; an ensemble member with it is
+    rejected."""
+    N = 32 ** 3
+    pb = params()
+    pf = P.make_params(32, gamma=1.4, C_=53.6, mu=1e-3, tau_p=(0.01,), fourier=FOURIER)
+    assert lib.pisoc_workspace_bytes(ctypes.byref(pf)) >= \
+        lib.pisoc_workspace_bytes(ctypes.byref(pb)) + 5 * 8 * N
+    assert lib.pisoc_ens_workspace_bytes(ctypes.byref(pf), 1) == 0
+
+
 def test_negative_tau_and_missing_dt_rejected(lib):
     p = params()
     p.tau_p[0] = -1.0
