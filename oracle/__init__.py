@@ -48,7 +48,7 @@ class OraParams(C.Structure):
         ("p_tol", C.c_double), ("p_maxit", C.c_int32),
         ("two_way", C.c_int32), ("gravity", C.c_double * 3),
         ("closure", C.c_int32), ("R_gas", C.c_double), ("cv", C.c_double),
-        ("kappa", C.c_double), ("T0", C.c_double),
+        ("kappa", C.c_double), ("T0", C.c_double), ("time_scheme", C.c_int32),
     ]
 
 
@@ -428,7 +428,7 @@ class Oracle:
     def __init__(self, n, rho, u, rho_p=None, *, gamma=1.4, C_=None, mu=1e-3, tau_p=(),
                  cfl=0.5, dt_growth=1.2, dt_fixed=0.0, dt_max=0.0, n_corr=2, n_mom_sweeps=4,
                  n_dust_sweeps=4, p_tol=1e-8, p_maxit=500, capture=False, two_way=False,
-                 gravity=(0.0, 0.0, 0.0), fourier=None, T=None):
+                 gravity=(0.0, 0.0, 0.0), fourier=None, T=None, bdf2=False):
         """fourier: None (barotropic) or dict(R=, cv=, kappa=, T0=) for the ideal
         gas with the energy equation; T: its initial temperature field."""
         if C_ is None:
@@ -446,6 +446,7 @@ class Oracle:
         prm.two_way = 1 if two_way else 0
         for d in range(3):
             prm.gravity[d] = gravity[d]
+        prm.time_scheme = 1 if bdf2 else 0
         if fourier is not None:
             prm.closure = FOURIER
             prm.R_gas, prm.cv, prm.kappa, prm.T0 = (fourier["R"], fourier["cv"], fourier["kappa"],

@@ -435,6 +435,10 @@ struct ora_state {
     double* fd[3];
     /* Fourier closure: temperature */
     double* T;
+    /* BDF2: the state at t^{n-1} */
+    double* rho_m1;
+    double* u_m1[3];
+    double* rho_p_m1[ORA_MAX_CLASSES];
     /* captured pressure systems of the last step, one set per corrector */
     double* sys_b[ORA_MAX_CORR];
     double* sys_w[ORA_MAX_CORR];
@@ -458,6 +462,8 @@ static int check_params(const ora_params* p) {
     if (p->n_classes < 0 || p->n_classes > ORA_MAX_CLASSES) return 0;
     if (!(p->gamma > 1.0) || !(p->C > 0.0) || !(p->mu >= 0.0)) return 0;
     if (p->closure != ORA_BAROTROPIC && p->closure != ORA_FOURIER) return 0;
+    if (p->time_scheme != ORA_BDF1 && p->time_scheme != ORA_BDF2) return 0;
+    if (p->time_scheme == ORA_BDF2 && (p->closure != ORA_BAROTROPIC || p->two_way)) return 0;
     if (p->closure == ORA_FOURIER &&
         (!(p->R_gas > 0.0) || !(p->cv > 0.0) || !(p->kappa >= 0.0) || !(p->T0 > 0.0)))
         return 0;
@@ -474,6 +480,9 @@ static void free_state(ora_state* s) {
     if (!s) return;
     free(s->rho);
     free(s->T);
+    free(s->rho_m1);
+    for (int d = 0; d < 3; ++d) free(s->u_m1[d]);
+    for (int c = 0; c < ORA_MAX_CLASSES; ++c) free(s->rho_p_m1[c]);
     for (int d = 0; d < 3; ++d) {
         free(s->u[d]);
         free(s->phi[d]);
@@ -548,6 +557,11 @@ int ora_create(const ora_params* prm, const double* rho, const double* u, const 
     if (prm->closure == ORA_FOURIER) {
         s->T = alloc_field(s->N);
         for (size_t P = 0; P < s->N; ++P) s->T[P] = prm->T0;
+    }
+    if (prm->time_scheme == ORA_BDF2) {   /* unused until a step has been taken */
+        s->rho_m1 = alloc_field(s->N);
+        for (int d = 0; d < 3; ++d) s->u_m1[d] = alloc_field(s->N);
+        for (int c = 0; c < prm->n_classes; ++c) s->rho_p_m1[c] = alloc_field(s->N);
     }
     *out = s;
     return ORA_OK;
@@ -631,12 +645,20 @@ static int one_step(ora_state* s, ora_info* info) {
         if (pr->dt_max > 0.0 && pr->dt_max < dt) dt = pr->dt_max;
     }
     if (!(dt > 0.0) || !isfinite(dt)) return ORA_ERR_INVALID;
+    /* time derivative d/dt y ~ (c0 y^{n+1} - c1 y^n + c2 y^{n-1}) / dt */
+    const int bdf2 = pr->time_scheme == ORA_BDF2;
+    const double om = bdf2 && isfinite(s->dt_prev) ? dt / s->dt_prev : 0.0;
+    const double c0 = (1.0 + 2.0 * om) / (1.0 + om), c1 = 1.0 + om, c2 = om * om / (1.0 + om);
 
     /* ---- 2. density predictor: rho* = rho^n - dt div(phi^n) ---- */
     NEWF(divphi);
     NEWF(rhos);
     ora_div_flux(n, s->phi[0], s->phi[1], s->phi[2], divphi);
-    for (size_t P = 0; P < N; ++P) rhos[P] = s->rho[P] - dt * divphi[P];
+    if (bdf2)
+        for (size_t P = 0; P < N; ++P)
+            rhos[P] = (c1 * s->rho[P] - c2 * s->rho_m1[P] - dt * divphi[P]) / c0;
+    else
+        for (size_t P = 0; P < N; ++P) rhos[P] = s->rho[P] - dt * divphi[P];
 
     /* ---- two-way coupling: the momentum equation is the mixture's.  Its
      * density rho_m = rho + rho_d (rho_d = sum_j rho_j), predicted as
@@ -674,7 +696,7 @@ static int one_step(ora_state* s, ora_info* info) {
     /* ---- 3. momentum coefficients and explicit source ---- */
     NEWF(aP);
     for (size_t P = 0; P < N; ++P)
-        aP[P] = rms[P] / dt + (9.0 / 16.0) * divfm[P] + 6.0 * mu / (h * h);
+        aP[P] = (bdf2 ? c0 : 1.0) * rms[P] / dt + (9.0 / 16.0) * divfm[P] + 6.0 * mu / (h * h);
     NEWF(divu);
     NEWF(gd0); NEWF(gd1); NEWF(gd2);
     double* gdivu[3] = {gd0, gd1, gd2};
@@ -684,7 +706,9 @@ static int one_step(ora_state* s, ora_info* info) {
     double* src[3] = {s0, s1, s2};
     for (int d = 0; d < 3; ++d)
         for (size_t P = 0; P < N; ++P) {
-            src[d][P] = rmn[P] * s->u[d][P] / dt + (mu / 3.0) * gdivu[d][P];
+            src[d][P] = (bdf2 ? c1 * rmn[P] * s->u[d][P] - c2 * s->rho_m1[P] * s->u_m1[d][P]
+                              : rmn[P] * s->u[d][P]) / dt +
+                        (mu / 3.0) * gdivu[d][P];
             if (pr->two_way) src[d][P] += (rmn[P] - mean_m) * pr->gravity[d];
         }
     NEWF(pn);
@@ -790,7 +814,7 @@ static int one_step(ora_state* s, ora_info* info) {
                 psidt[P] = 1.0 / (Rg * Ts[P]) / dt;
             } else {
                 p0[P] = Cc * pow(rhok[P], g);
-                psidt[P] = 1.0 / (g * Cc * pow(rhok[P], g - 1.0)) / dt;
+                psidt[P] = (bdf2 ? c0 : 1.0) / (g * Cc * pow(rhok[P], g - 1.0)) / dt;
             }
         }
         /* 5.2 HbyA = H(u)/a_P with H(u) = s - N(u) */
@@ -812,7 +836,11 @@ static int one_step(ora_state* s, ora_info* info) {
             }
         }
         ora_div_flux(n, fa[0], fa[1], fa[2], dv);
-        for (size_t P = 0; P < N; ++P) b[P] = -((rhok[P] - s->rho[P]) / dt + dv[P]);
+        if (bdf2)
+            for (size_t P = 0; P < N; ++P)
+                b[P] = -((c0 * rhok[P] - c1 * s->rho[P] + c2 * s->rho_m1[P]) / dt + dv[P]);
+        else
+            for (size_t P = 0; P < N; ++P) b[P] = -((rhok[P] - s->rho[P]) / dt + dv[P]);
         /* 5.6-5.7 solve M p' = b from p' = 0 */
         memset(x, 0, N * sizeof(double));
         double relres = 0.0;
@@ -842,7 +870,11 @@ static int one_step(ora_state* s, ora_info* info) {
             for (size_t P = 0; P < N; ++P) phin[d][P] = phiH[d][P] - Kf[d][P] * A * sg[P];
         }
         ora_div_flux(n, phin[0], phin[1], phin[2], dv);
-        for (size_t P = 0; P < N; ++P) rhok[P] = s->rho[P] - dt * dv[P];
+        if (bdf2)
+            for (size_t P = 0; P < N; ++P)
+                rhok[P] = (c1 * s->rho[P] - c2 * s->rho_m1[P] - dt * dv[P]) / c0;
+        else
+            for (size_t P = 0; P < N; ++P) rhok[P] = s->rho[P] - dt * dv[P];
         ora_grad(n, pk, tface[0], tface[1], tface[2]);
         for (int d = 0; d < 3; ++d)
             for (size_t P = 0; P < N; ++P) ucur[d][P] = hbya[d][P] - tface[d][P] / aP[P];
@@ -865,7 +897,8 @@ static int one_step(ora_state* s, ora_info* info) {
             for (size_t P = 0; P < N; ++P) {
                 double conv = 0.0;
                 for (int e = 0; e < 3; ++e) conv += ucur[e][P] * gu[d][e][P];
-                acc[d][P] = (ucur[d][P] - s->u[d][P]) / dt + conv;
+                acc[d][P] = (bdf2 ? c0 * ucur[d][P] - c1 * s->u[d][P] + c2 * s->u_m1[d][P]
+                                  : ucur[d][P] - s->u[d][P]) / dt + conv;
             }
         /* class-independent face factor D_d = I4(rho^{n+1}) (I4(a_d) - g_d) A:
          * the drift u_j - u = tau_j (g - Du/Dt) at the faces */
@@ -904,7 +937,8 @@ static int one_step(ora_state* s, ora_info* info) {
                     }
             /* the diagonal of the implicit equation below must stay positive */
             for (size_t P = 0; P < N; ++P)
-                if (!(rhok[P] / dt + (9.0 / 16.0) * divG[P] > 0.0)) flags |= ORA_FLAG_DUST_DIAG;
+                if (!((bdf2 ? c0 : 1.0) * rhok[P] / dt + (9.0 / 16.0) * divG[P] > 0.0))
+                    flags |= ORA_FLAG_DUST_DIAG;
             for (size_t P = 0; P < N; ++P) Y[P] = rj[P] / s->rho[P];
             /* implicit Euler for rho Y: Jacobi sweeps */
             for (int sweep = 0; sweep < pr->n_dust_sweeps; ++sweep) {
@@ -915,7 +949,11 @@ static int one_step(ora_state* s, ora_info* info) {
                 ora_div_flux(n, tface[0], tface[1], tface[2], ry);
                 for (size_t P = 0; P < N; ++P) {
                     double off = ry[P] - (9.0 / 16.0) * divG[P] * Y[P];
-                    Yn[P] = (rj[P] / dt - off) / (rhok[P] / dt + (9.0 / 16.0) * divG[P]);
+                    if (bdf2)
+                        Yn[P] = ((c1 * rj[P] - c2 * s->rho_p_m1[c][P]) / dt - off) /
+                                (c0 * rhok[P] / dt + (9.0 / 16.0) * divG[P]);
+                    else
+                        Yn[P] = (rj[P] / dt - off) / (rhok[P] / dt + (9.0 / 16.0) * divG[P]);
                 }
                 double* tmp = Y;
                 Y = Yn;
@@ -932,7 +970,8 @@ static int one_step(ora_state* s, ora_info* info) {
             ora_div_flux(n, tface[0], tface[1], tface[2], ry);
             rpn[c] = pool_get(s, slot++);
             for (size_t P = 0; P < N; ++P) {
-                rpn[c][P] = rj[P] - dt * ry[P];
+                rpn[c][P] = bdf2 ? (c1 * rj[P] - c2 * s->rho_p_m1[c][P] - dt * ry[P]) / c0
+                                 : rj[P] - dt * ry[P];
                 if (!isfinite(rpn[c][P])) flags |= ORA_FLAG_DUST_NONFINITE;
                 else if (rpn[c][P] < 0.0) flags |= ORA_FLAG_DUST_NEG;
             }
@@ -962,6 +1001,12 @@ static int one_step(ora_state* s, ora_info* info) {
         if ((flags & (ORA_FLAG_DUST_NEG | ORA_FLAG_DUST_DIAG | ORA_FLAG_DUST_COURANT)) &&
             status == ORA_OK)
             status = ORA_WARN_DUST;
+        if (bdf2) {   /* t^n becomes t^{n-1} */
+            memcpy(s->rho_m1, s->rho, N * sizeof(double));
+            for (int d = 0; d < 3; ++d) memcpy(s->u_m1[d], s->u[d], N * sizeof(double));
+            for (int c = 0; c < pr->n_classes; ++c)
+                memcpy(s->rho_p_m1[c], s->rho_p[c], N * sizeof(double));
+        }
         memcpy(s->rho, rhok, N * sizeof(double));
         if (fourier) memcpy(s->T, Ts, N * sizeof(double));
         for (int d = 0; d < 3; ++d) {

@@ -71,7 +71,16 @@ typedef struct {
      * temperature, see ora_set_temperature) */
     int32_t closure;
     double R_gas, cv, kappa, T0;
+    /* time scheme: 0 backward Euler (BDF1); 1 BDF2 with variable steps,
+     * d/dt y ~ (c0 y^{n+1} - c1 y^n + c2 y^{n-1}) / dt, w = dt / dt_prev,
+     * c0 = (1 + 2w)/(1 + w), c1 = 1 + w, c2 = w^2/(1 + w) (the first step,
+     * with no previous one, is BDF1: w = 0).  BDF2 takes the barotropic,
+     * one-way step only. */
+    int32_t time_scheme;
 } ora_params;
+
+#define ORA_BDF1 0
+#define ORA_BDF2 1
 
 #define ORA_BAROTROPIC 0
 #define ORA_FOURIER 1
