@@ -157,9 +157,19 @@ typedef struct {
                                   > 0, >= 0) */
     double T0;                 /* FOURIER: initial uniform temperature (> 0); see
                                   pisoc_set_temperature */
+    int32_t time_scheme;       /* PISOC_BDF1: backward Euler throughout (the step above);
+                                  PISOC_BDF2: variable-step BDF2, d/dt y ~ (c0 y^{n+1} -
+                                  c1 y^n + c2 y^{n-1})/dt with w = dt/dt_prev, c0 =
+                                  (1+2w)/(1+w), c1 = 1+w, c2 = w^2/(1+w) (backward Euler
+                                  on the first step), in the density predictor, the
+                                  momentum coefficients and source, the corrector's
+                                  defect, compressibility (c0 psi/dt) and density update,
+                                  and the dust's acceleration and transport.  BDF2 needs
+                                  FP64, the barotropic closure, two_way = 0 and one grid */
 } pisoc_params;
 
 enum { PISOC_BAROTROPIC = 0, PISOC_FOURIER = 1 };
+enum { PISOC_BDF1 = 0, PISOC_BDF2 = 1 };
 
 typedef struct {
     double t, dt, courant;           /* time after the step, dt, sigma*dt */

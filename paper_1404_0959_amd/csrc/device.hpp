@@ -35,7 +35,23 @@ struct Phys {
     double R, cv, kappa;
     const double* tn;
     const double* ts;
+    // BDF2 (FP64 single grids, gathered kernels): the state at t^{n-1}
+    // (density deviation, velocity, and one class's bulk density, set per
+    // class); the coefficients are DevState::bdf
+    int bdf2;
+    const double* rm1;
+    const double* um1;
+    const double* rjm1;
 };
+
+// Variable-step BDF2 coefficients, d/dt y ~ (c0 y^{n+1} - c1 y^n + c2 y^{n-1}) / dt
+// with w = dt / dt_prev (w = 0, backward Euler, when there is no previous step).
+__host__ __device__ inline void bdf2_coef(double dt, double dt_prev, double (&c)[3]) {
+    const double w = isfinite(dt_prev) ? dt / dt_prev : 0.0;
+    c[0] = (1.0 + 2.0 * w) / (1.0 + w);
+    c[1] = 1.0 + w;
+    c[2] = w * w / (1.0 + w);
+}
 
 // The compressibility factor of the corrector: psi = rho / (gamma_psi p) with
 // gamma_psi = gamma for the barotropic closure (d rho / d p of C rho^gamma)
@@ -90,6 +106,8 @@ struct DevState {
     double rhom_mean;
     // the dust's Courant number of the step (max over the classes)
     double courant_dust;
+    // BDF2 coefficients of the step (c0, c1, c2), written by the predictor
+    double bdf[3];
 };
 
 // A cell and the periodic offsets to the cells up to two steps away along

@@ -196,7 +196,11 @@ __global__ void __launch_bounds__(kBlock) k_predict(Phys ph, DevState* st, const
     double sg[1];
     reduce_member<1, 1u>(part_cfl, nb, ph.batch, mem_, sg);
     const double dtd = predict_dt(sg[0], (st + mem_)->dt_prev, dt_fixed, cfl, growth, dt_max);
+    double bc[3] = {1.0, 1.0, 0.0};
+    if (ph.bdf2) bdf2_coef(dtd, (st + mem_)->dt_prev, bc);
     if (MEMBER_FIRST()) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) (st + mem_)->bdf[q] = bc[q];
         if (!(dtd > 0.0) || !isfinite(dtd)) (st + mem_)->flags |= 16;  // bad dt
         (st + mem_)->sigma = sg[0];
         (st + mem_)->dt = dtd;
@@ -219,6 +223,15 @@ __global__ void __launch_bounds__(kBlock) k_predict(Phys ph, DevState* st, const
                  (st + mem_)->p_ref, ph.gamma, r, a, dv, p);
     if (ph.fourier)   // ideal gas at T^n
         p = (T)(((st + mem_)->rho_ref + (double)rnP) * ph.R * ph.tn[P] - (st + mem_)->p_ref);
+    if (ph.bdf2) {    // rho* = (c1 rho^n - c2 rho^{n-1} - dt div phi) / c0, a_P with c0 rho*/dt
+        double dphi = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dphi += (double)fp[d] - (double)fm[d];
+        dphi *= ph.inv_V;
+        const double rr = (bc[1] * (double)rnP - bc[2] * ph.rm1[P] - dtd * dphi) / bc[0];
+        r = (T)rr;
+        a = (T)(bc[0] * ((st + mem_)->rho_ref + rr) / dtd + 0.5625 * dphi + 6.0 * ph.mu * ph.inv_h2);
+    }
     rs[P] = r;
     aP[P] = a;
     divu[P] = dv;
@@ -253,6 +266,14 @@ __global__ void __launch_bounds__(kBlock) k_mom_source(Phys ph, const DevState* 
     loads_issued();
     T out[3];
     mom_source_cell(dv, uv, rho, dt, m3, inv_h, out);
+    if (ph.bdf2) {   // (c1 rho^n u^n - c2 rho^{n-1} u^{n-1}) / dt
+        const double* bc = (st + mem_)->bdf;
+        const double rm = (st + mem_)->rho_ref + ph.rm1[P];
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            out[m] = (T)((bc[1] * (double)rho * (double)uv[m] - bc[2] * rm * ph.um1[m * N + P]) /
+                         (double)dt + (double)m3 * (double)dgauss13(dv, m, inv_h));
+    }
 #pragma unroll
     for (int m = 0; m < 3; ++m) s[m * N + P] = out[m];
     END_CELLS
@@ -597,7 +618,8 @@ template <typename T>
 __device__ inline void corr_rhs_cell(const T (&wv)[13], const T (&rv)[13], const T (&hl)[3][5],
                                      const T (&pv)[7], T rnP, double dt, double rref, double pref,
                                      double gamma, double A, double inv_V, double inv_h,
-                                     double inv_h2, double& b, T& dgT, T (&phf)[3]) {
+                                     double inv_h2, double& b, T& dgT, T (&phf)[3],
+                                     const double* bc = nullptr, double rm1P = 0.0) {
     double divF = 0.0, sumK = 0.0;
     const double p0P = (double)pv[0];
 #pragma unroll
@@ -614,9 +636,12 @@ __device__ inline void corr_rhs_cell(const T (&wv)[13], const T (&rv)[13], const
             if (s == 0) phf[d] = (T)ph_f;
         }
     }
-    b = -(((double)rv[0] - (double)rnP) / dt + divF * inv_V);
+    if (bc)   // BDF2: (c0 rho_k - c1 rho^n + c2 rho^{n-1}) / dt and c0 psi / dt
+        b = -((bc[0] * (double)rv[0] - bc[1] * (double)rnP + bc[2] * rm1P) / dt + divF * inv_V);
+    else
+        b = -(((double)rv[0] - (double)rnP) / dt + divF * inv_V);
     const double rho = rref + (double)rv[0];
-    const double psidt = rho / (gamma * (pref + p0P)) / dt;
+    const double psidt = (bc ? bc[0] : 1.0) * rho / (gamma * (pref + p0P)) / dt;
     dgT = (T)(psidt + sumK * inv_h2);
 }
 
@@ -667,7 +692,8 @@ __global__ void __launch_bounds__(kBlock) k_corr_rhs(
     double b;
     T dgT, phf[3];
     corr_rhs_cell(wv, rv, hl, pv, rnP, dt, rref, pref, gamma_psi(ph), ph.A, ph.inv_V, ph.inv_h,
-                  ph.inv_h2, b, dgT, phf);
+                  ph.inv_h2, b, dgT, phf, ph.bdf2 ? (st + mem_)->bdf : nullptr,
+                  ph.bdf2 ? ph.rm1[P] : 0.0);
     corr_rhs_store(P, N, b, dgT, phf, pref + (double)pv[0], phiH, rvec, diag, snap_b, snap_diag,
                    snap_p0, b64, v);
     END_CELLS
@@ -2058,6 +2084,13 @@ __global__ void __launch_bounds__(kBlock) k_corr_update(Phys ph, const DevState*
     loads_issued();
     T r, um[3];
     corr_update_cell(pv, fp, fm, hb, rnP, a, dt, inv_V, inv_h, r, um);
+    if (ph.bdf2) {   // rho_k = (c1 rho^n - c2 rho^{n-1} - dt div phi_k) / c0
+        const double* bc = (st + mem_)->bdf;
+        double dphi = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dphi += (double)fp[d] - (double)fm[d];
+        r = (T)((bc[1] * (double)rnP - bc[2] * ph.rm1[P] - (double)dt * dphi * ph.inv_V) / bc[0]);
+    }
     rk[P] = r;
     double usq = 0.0;
 #pragma unroll
@@ -2106,6 +2139,16 @@ __global__ void __launch_bounds__(kBlock) k_dudt(Phys ph, const DevState* st,
     loads_issued();
     T out[3];
     dudt_cell(uv, u0, dt, inv_h, out);
+    if (ph.bdf2) {   // (c0 u^{n+1} - c1 u^n + c2 u^{n-1}) / dt + (u.grad)u
+        const double* bc = (st + mem_)->bdf;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const T conv = uv[0][0] * dgauss13(uv[m], 0, inv_h) + uv[1][0] * dgauss13(uv[m], 1, inv_h) +
+                           uv[2][0] * dgauss13(uv[m], 2, inv_h);
+            out[m] = (T)((bc[0] * (double)uv[m][0] - bc[1] * (double)u0[m] + bc[2] * ph.um1[m * N + P]) /
+                         (double)dt) + conv;
+        }
+    }
 #pragma unroll
     for (int m = 0; m < 3; ++m) acc[m * N + P] = out[m];
     END_CELLS
@@ -2194,7 +2237,22 @@ __global__ void __launch_bounds__(kBlock) k_dust_sweep(Phys ph, const DevState* 
     const T rj = rhoj[P], r1P = r1[P];
     loads_issued();
     T dg;
-    Yout[P] = dust_sweep_cell(yv, gpv, gmv, rj, r1P, dt, inv_V, (T)(st + mem_)->rho_ref, dg);
+    if (ph.bdf2) {   // diagonal c0 rho^{n+1}/dt + (9/16) div G, right side (c1 rho_j - c2 rho_j^{n-1})/dt
+        const double* bc = (st + mem_)->bdf;
+        T conv = T(0), dG = T(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            conv += gpv[d] * i4g(yv, d, 0) - gmv[d] * i4g(yv, d, -1);
+            dG += gpv[d] - gmv[d];
+        }
+        conv *= inv_V;
+        dG *= inv_V;
+        const T off = conv - T(0.5625) * dG * yv[0];
+        dg = (T)(bc[0] * (rref + (double)r1P) / (double)dt) + T(0.5625) * dG;
+        Yout[P] = ((T)((bc[1] * (double)rj - bc[2] * ph.rjm1[P]) / (double)dt) - off) / dg;
+    } else {
+        Yout[P] = dust_sweep_cell(yv, gpv, gmv, rj, r1P, dt, inv_V, (T)(st + mem_)->rho_ref, dg);
+    }
     if (CHECK) {
         v[0] = fmax(v[0], -(double)dg);
         v[1] = fmax(v[1], courant_rate(gpv, gmv, r1P, rref, ph.V));
@@ -2236,7 +2294,10 @@ __global__ void __launch_bounds__(kBlock) k_dust_finish(Phys ph, const DevState*
     if (fdo)
 #pragma unroll
         for (int d = 0; d < 3; ++d) fdo[d * N + P] = (first ? T(0) : fdo[d * N + P]) + F[d * N + P];
-    const T out = rhoj[P] - dt * dF * inv_V;
+    const T out = ph.bdf2   // (c1 rho_j - c2 rho_j^{n-1} - dt div F) / c0
+                      ? (T)(((st + mem_)->bdf[1] * (double)rhoj[P] - (st + mem_)->bdf[2] * ph.rjm1[P] -
+                             (double)(dt * dF * inv_V)) / (st + mem_)->bdf[0])
+                      : rhoj[P] - dt * dF * inv_V;
     rhoj1[P] = out;
     v[0] += (double)out;
     v[1] = fmax(v[1], -(double)out);

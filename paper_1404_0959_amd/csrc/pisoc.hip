@@ -74,6 +74,7 @@ struct Layout {
     size_t wpk, nx4, na, nb, ny, bsave;  // learned guess: packed weights, activations
     size_t xprev;  // previous-step guess: each corrector's last solution
     size_t t0, t1, tw, eaT, esT;  // Fourier closure: T (two rotating), sweep scratch, a_T, s_T
+    size_t rm1, um1, rjm1;        // BDF2: rho, u, rho_j at t^{n-1}
     size_t total;
     unsigned max_blocks;     // column length of the partials (all members)
 };
@@ -184,6 +185,10 @@ bool valid_params(const pisoc_params* p, std::string* why) {
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(p->gravity[d])) return fail("gravity must be finite");
     if (p->closure != PISOC_BAROTROPIC && p->closure != PISOC_FOURIER) return fail("unknown closure");
+    if (p->time_scheme != PISOC_BDF1 && p->time_scheme != PISOC_BDF2) return fail("unknown time scheme");
+    if (p->time_scheme == PISOC_BDF2 &&
+        (p->precision != PISOC_FP64 || p->closure != PISOC_BAROTROPIC || p->two_way))
+        return fail("BDF2 needs FP64, the barotropic closure and two_way = 0");
     if (p->closure == PISOC_FOURIER) {
         if (!(p->R_gas > 0.0) || !(p->cv > 0.0) || !(p->kappa >= 0.0) || !(p->T0 > 0.0))
             return fail("Fourier closure needs R_gas > 0, cv > 0, kappa >= 0 and T0 > 0");
@@ -225,6 +230,11 @@ Layout make_layout(const pisoc_params* p, int batch) {
     }
     L.snap = p->capture ? take((p->guess != PISOC_GUESS_ZERO ? 10 : 8) * sizeof(double) * N)
                         : 0;
+    if (p->time_scheme == PISOC_BDF2) {   // FP64 only
+        L.rm1 = take(sizeof(double) * N);
+        L.um1 = take(3 * sizeof(double) * N);
+        L.rjm1 = take(sizeof(double) * N * (size_t)std::max(p->n_classes, 1));
+    }
     if (p->closure == PISOC_FOURIER) {   // FP64 only
         L.t0 = take(sizeof(double) * N);
         L.t1 = take(sizeof(double) * N);
@@ -285,6 +295,7 @@ struct pisoc_ctx {
     size_t rn, rk, phin, phik, rhop, rhop1;
     size_t fdn, fdk;   // two-way coupling: dust mass fluxes of the last step / this one
     size_t tn, tk;     // Fourier closure: T^n / T* of the step being enqueued
+    size_t rm1, um1, rjm1;   // BDF2: the state at t^{n-1}
     double t;
     int64_t steps;
     int pred_first[PISOC_MAX_CORR];  // CG iterations of the last first solve (all members)
@@ -385,6 +396,7 @@ Phys make_phys(const pisoc_params* p, const Launch& L, int batch) {
     ph.mu = p->mu;
     for (int d = 0; d < 3; ++d) ph.g[d] = p->gravity[d];
     ph.fourier = p->closure == PISOC_FOURIER ? 1 : 0;
+    ph.bdf2 = p->time_scheme == PISOC_BDF2 ? 1 : 0;
     ph.R = p->R_gas;
     ph.cv = p->cv;
     ph.kappa = p->kappa;
@@ -760,12 +772,14 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
             });
             T* yin = S.Ya;
             T* yout = S.Yb;
+            Phys phc = ph;   // BDF2: this class's bulk density at t^{n-1}
+            if (ph.bdf2) phc.rjm1 = ph.rjm1 + c * N;
             for (int i = 0; i < p.n_dust_sweeps; ++i) {
                 // the first sweep also checks the implicit diagonal (the same in every sweep)
                 double* chk = i == 0 ? ctx->part(PS_DDIAG + 2 * c) : nullptr;
                 timed(ctx, KC_DUST_SWEEP, 7, -1, [&] {
                     const unsigned nb =
-                        O::dust_sweep(L, ctx->TL, s, ph, st, yin, yout, S.G, S.rj + c * N, S.rk, chk);
+                        O::dust_sweep(L, ctx->TL, s, phc, st, yin, yout, S.G, S.rj + c * N, S.rk, chk);
                     if (chk) nb_diag = nb;
                 });
                 std::swap(yin, yout);
@@ -782,7 +796,7 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
             } else {
                 timed(ctx, KC_DUST_FACEFLUX, 7, -1, [&] { O::dust_faceflux(L, s, ph, yin, S.G); });
                 timed(ctx, KC_DUST_FINISH, 5 + fdw, -1, [&] {
-                    O::dust_finish(L, s, ph, st, S.rj + c * N, S.G, S.rj1 + c * N,
+                    O::dust_finish(L, s, phc, st, S.rj + c * N, S.G, S.rj1 + c * N,
                                    ctx->part(PS_DUST + 2 * c), S.fdk, c == 0);
                 });
             }
@@ -1006,6 +1020,11 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
         ctx->ph.tn = ctx->f<double>(ctx->tn);
         ctx->ph.ts = ctx->f<double>(ctx->tk);
     }
+    if (ctx->ph.bdf2) {      // the state at t^{n-1}
+        ctx->ph.rm1 = ctx->f<double>(ctx->rm1);
+        ctx->ph.um1 = ctx->f<double>(ctx->um1);
+        ctx->ph.rjm1 = ctx->f<double>(ctx->rjm1);
+    }
     enqueue_front<T>(ctx, S, cfl_ready);
     // with the audit on, an eager step takes this step's decision and a
     // captured one the verdict it was built with (audit_decide_capture)
@@ -1060,10 +1079,29 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
 
 // Host-side rotation after an accepted step (period 2).
 void rotate(pisoc_ctx* ctx) {
-    std::swap(ctx->rn, ctx->rk);
+    const bool bdf2 = ctx->prm.time_scheme == PISOC_BDF2;
+    if (bdf2) {   // t^n becomes t^{n-1}; its old buffers take the next step's values
+        size_t t = ctx->rm1;
+        ctx->rm1 = ctx->rn;
+        ctx->rn = ctx->rk;
+        ctx->rk = t;
+    } else {
+        std::swap(ctx->rn, ctx->rk);
+    }
     std::swap(ctx->phin, ctx->phik);
     std::swap(ctx->u_idx[0], ctx->u_idx[ctx->ucur_slot]);
-    if (ctx->prm.n_classes > 0) std::swap(ctx->rhop, ctx->rhop1);
+    // the old u^n now sits in a work slot: it becomes u^{n-1}
+    if (bdf2) std::swap(ctx->lay.u3[ctx->u_idx[ctx->ucur_slot]], ctx->um1);
+    if (ctx->prm.n_classes > 0) {
+        if (bdf2) {
+            size_t t = ctx->rjm1;
+            ctx->rjm1 = ctx->rhop;
+            ctx->rhop = ctx->rhop1;
+            ctx->rhop1 = t;
+        } else {
+            std::swap(ctx->rhop, ctx->rhop1);
+        }
+    }
     // two-way with dust: this step's F_d becomes the next step's (without dust
     // both stay zero)
     if (ctx->prm.two_way && ctx->prm.n_classes > 0) std::swap(ctx->fdn, ctx->fdk);
@@ -1189,6 +1227,8 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     // the Fourier closure runs the gathered field kernels (the tiled z-marches
     // evaluate the barotropic closure inline); the CG kernel is closure-free
     if (prm->closure == PISOC_FOURIER) ctx->TL = Launch{};
+    // BDF2 runs the gathered field kernels as well (the tiled ones hold backward Euler)
+    if (prm->time_scheme == PISOC_BDF2) ctx->TL = Launch{};
     ctx->L = make_launch(prm->n, batch);
     ctx->ph = make_phys(prm, ctx->L, batch);
     ctx->st = reinterpret_cast<DevState*>(ctx->ws + lay.state);
@@ -1337,6 +1377,21 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
         ctx->tn = lay.t0;
         ctx->tk = lay.t1;
         fill_value(s, ctx->f<double>(ctx->tn), NT, prm->T0);
+    }
+    if (prm->time_scheme == PISOC_BDF2) {
+        // t^{n-1} starts as the initial state (weighted by c2 = 0 in the first
+        // step, but it must hold finite values)
+        ctx->rm1 = lay.rm1;
+        ctx->um1 = lay.um1;
+        ctx->rjm1 = lay.rjm1;
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->f<double>(ctx->rm1), ctx->f<double>(ctx->rn),
+                                    NT * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->f<double>(ctx->um1), ctx->f<double>(lay.u3[0]),
+                                    3 * NT * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (prm->n_classes > 0)
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->f<double>(ctx->rjm1), ctx->f<double>(ctx->rhop),
+                                        (size_t)prm->n_classes * NT * sizeof(double),
+                                        hipMemcpyDeviceToDevice, s));
     }
     if (prm->guess == PISOC_GUESS_LEARNED)
         net_pack_forward(s, reinterpret_cast<const float*>(prm->d_guess_weights), ctx->ws + lay.wpk);
@@ -1931,8 +1986,8 @@ bool ens_classes(const pisoc_params* members, int32_t count, std::vector<std::ve
     }
     for (int m = 0; m < count; ++m) {
         if (!valid_params(&members[m], why)) return false;
-        if (members[m].closure != PISOC_BAROTROPIC) {
-            if (why) *why = "ensembles take the barotropic closure only";
+        if (members[m].closure != PISOC_BAROTROPIC || members[m].time_scheme != PISOC_BDF1) {
+            if (why) *why = "ensembles take the barotropic closure and backward Euler only";
             return false;
         }
         if (!same_class_params(members[m], members[0])) {

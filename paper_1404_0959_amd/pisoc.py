@@ -29,6 +29,7 @@ FIELD_PSOLVE_B, FIELD_PSOLVE_X, FIELD_P_PREV, FIELD_PSOLVE_DIAG = 32, 64, 128, 2
 FIELD_USTAR, FIELD_GUESS, FIELD_GUESS_X0, FIELD_PSOLVE_W = 512, 1024, 2048, 4096
 FIELD_PSOLVE_PSIDT, FIELD_T = 8192, 16384
 BAROTROPIC, FOURIER = 0, 1
+BDF1, BDF2 = 0, 1
 
 EXPORTED = [
     "pisoc_workspace_bytes", "pisoc_init", "pisoc_step", "pisoc_fields", "pisoc_get_stats",
@@ -68,7 +69,7 @@ class Params(C.Structure):
         ("capture", C.c_int32), ("guess_audit", C.c_int32),
         ("two_way", C.c_int32), ("gravity", C.c_double * 3),
         ("closure", C.c_int32), ("R_gas", C.c_double), ("cv", C.c_double),
-        ("kappa", C.c_double), ("T0", C.c_double),
+        ("kappa", C.c_double), ("T0", C.c_double), ("time_scheme", C.c_int32),
     ]
 
 
@@ -231,9 +232,9 @@ def make_params(n, *, gamma, C_, mu, tau_p=(), cfl=0.5, dt_growth=1.2, dt_fixed=
                 n_corr=2, n_mom_sweeps=4, n_dust_sweeps=4, p_tol=1e-8, p_maxit=500,
                 precision=FP64, guess=GUESS_ZERO, guess_weights=None, inner_tol=1e-7,
                 max_refine=20, capture=False, guess_audit=0, two_way=False,
-                gravity=(0.0, 0.0, 0.0), fourier=None) -> Params:
+                gravity=(0.0, 0.0, 0.0), fourier=None, bdf2=False) -> Params:
     """fourier: None (barotropic) or dict(R=, cv=, kappa=, T0=) for the ideal gas
-    with the energy equation."""
+    with the energy equation; bdf2: the variable-step BDF2 time scheme."""
     p = Params()
     p.n = n
     p.n_classes = len(tau_p)
@@ -254,6 +255,7 @@ def make_params(n, *, gamma, C_, mu, tau_p=(), cfl=0.5, dt_growth=1.2, dt_fixed=
     if fourier is not None:
         p.closure = FOURIER
         p.R_gas, p.cv, p.kappa, p.T0 = fourier["R"], fourier["cv"], fourier["kappa"], fourier["T0"]
+    p.time_scheme = BDF2 if bdf2 else BDF1
     return p
 
 

@@ -84,6 +84,20 @@ def test_fourier_params_rejected(lib, change):
     assert lib.pisoc_workspace_bytes(ctypes.byref(p)) == 0
 
 
+@pytest.mark.parametrize("change", [
+    dict(time_scheme=2), dict(precision=P.FP32_REFINED, inner_tol=1e-6), dict(two_way=1),
+    dict(closure=P.FOURIER, R_gas=1.0, cv=2.5, kappa=0.0, T0=1.0),
+])
+def test_bdf2_params_rejected(lib, change):
+    """BDF2 runs in FP64 with the barotropic closure and one-way coupling."""
+    p = P.make_params(32, gamma=1.4, C_=53.6, mu=1e-3, tau_p=(0.01,), bdf2=True)
+    assert lib.pisoc_workspace_bytes(ctypes.byref(p)) > 0
+    assert lib.pisoc_ens_workspace_bytes(ctypes.byref(p), 1) == 0
+    for k, v in change.items():
+        setattr(p, k, v)
+    assert lib.pisoc_workspace_bytes(ctypes.byref(p)) == 0
+
+
 def test_fourier_workspace_and_ensemble_rejection(lib):
     """The closure adds five FP64 cell fields; an ensemble member with it is
     rejected."""
