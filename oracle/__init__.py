@@ -26,6 +26,7 @@ OK, WARN_NOT_CONVERGED, WARN_DUST, ERR_INVALID, ERR_DIVERGED = 0, 1, 3, -1, -3
 FLAG_PCG_MAXIT, FLAG_NONFINITE, FLAG_RHO_NONPOS, FLAG_KFACE_NONPOS = 1, 2, 4, 8
 FLAG_DUST_NEG, FLAG_DUST_NONFINITE, FLAG_DUST_DIAG, FLAG_DUST_COURANT = 64, 128, 256, 512
 DUST_COURANT_MAX = 0.638
+FLAG_MOM_MAXIT = 1024
 
 RHO, U, PHI, RHO_P, P, T = 0, 1, 2, 3, 4, 5
 BAROTROPIC, FOURIER = 0, 1
@@ -49,6 +50,7 @@ class OraParams(C.Structure):
         ("two_way", C.c_int32), ("gravity", C.c_double * 3),
         ("closure", C.c_int32), ("R_gas", C.c_double), ("cv", C.c_double),
         ("kappa", C.c_double), ("T0", C.c_double), ("time_scheme", C.c_int32),
+        ("mom_tol", C.c_double), ("mom_maxit", C.c_int32),
     ]
 
 
@@ -58,6 +60,7 @@ class OraInfo(C.Structure):
         ("pcg_iters", C.c_int32 * MAX_CORR), ("pcg_relres", C.c_double * MAX_CORR),
         ("flags", C.c_int32), ("mass_gas", C.c_double),
         ("mass_p", C.c_double * MAX_CLASSES), ("courant_dust", C.c_double),
+        ("mom_iters", C.c_int32), ("mom_relres", C.c_double),
     ]
 
 
@@ -428,7 +431,8 @@ class Oracle:
     def __init__(self, n, rho, u, rho_p=None, *, gamma=1.4, C_=None, mu=1e-3, tau_p=(),
                  cfl=0.5, dt_growth=1.2, dt_fixed=0.0, dt_max=0.0, n_corr=2, n_mom_sweeps=4,
                  n_dust_sweeps=4, p_tol=1e-8, p_maxit=500, capture=False, two_way=False,
-                 gravity=(0.0, 0.0, 0.0), fourier=None, T=None, bdf2=False):
+                 gravity=(0.0, 0.0, 0.0), fourier=None, T=None, bdf2=False, mom_tol=0.0,
+                 mom_maxit=200):
         """fourier: None (barotropic) or dict(R=, cv=, kappa=, T0=) for the ideal
         gas with the energy equation; T: its initial temperature field."""
         if C_ is None:
@@ -447,6 +451,7 @@ class Oracle:
         for d in range(3):
             prm.gravity[d] = gravity[d]
         prm.time_scheme = 1 if bdf2 else 0
+        prm.mom_tol, prm.mom_maxit = mom_tol, mom_maxit
         if fourier is not None:
             prm.closure = FOURIER
             prm.R_gas, prm.cv, prm.kappa, prm.T0 = (fourier["R"], fourier["cv"], fourier["kappa"],
@@ -490,7 +495,8 @@ class Oracle:
                             pcg_iters=list(r.pcg_iters[: self.prm.n_corr]),
                             pcg_relres=list(r.pcg_relres[: self.prm.n_corr]),
                             flags=r.flags, mass_gas=r.mass_gas,
-                            mass_p=list(r.mass_p[: self.K]), courant_dust=r.courant_dust))
+                            mass_p=list(r.mass_p[: self.K]), courant_dust=r.courant_dust,
+                            mom_iters=r.mom_iters, mom_relres=r.mom_relres))
         return st, out
 
     def get(self, which, corr=0):

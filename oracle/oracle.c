@@ -449,7 +449,7 @@ struct ora_state {
     double* sys_diag[ORA_MAX_CORR];
     double* sys_ustar[3];
     /* work arrays of the step, allocated on first use and kept */
-    double* pool[128];
+    double* pool[256];
 };
 
 static double* pool_get(ora_state* s, int slot) {
@@ -463,6 +463,8 @@ static int check_params(const ora_params* p) {
     if (!(p->gamma > 1.0) || !(p->C > 0.0) || !(p->mu >= 0.0)) return 0;
     if (p->closure != ORA_BAROTROPIC && p->closure != ORA_FOURIER) return 0;
     if (p->time_scheme != ORA_BDF1 && p->time_scheme != ORA_BDF2) return 0;
+    if (!(p->mom_tol >= 0.0) || !(p->mom_tol < 1.0) || (p->mom_tol > 0.0 && p->mom_maxit < 1))
+        return 0;
     if (p->time_scheme == ORA_BDF2 && (p->closure != ORA_BAROTROPIC || p->two_way)) return 0;
     if (p->closure == ORA_FOURIER &&
         (!(p->R_gas > 0.0) || !(p->cv > 0.0) || !(p->kappa >= 0.0) || !(p->T0 > 0.0)))
@@ -499,7 +501,7 @@ static void free_state(ora_state* s) {
         free(s->sys_diag[c]);
     }
     for (int d = 0; d < 3; ++d) free(s->sys_ustar[d]);
-    for (int i = 0; i < 128; ++i) free(s->pool[i]);
+    for (int i = 0; i < 256; ++i) free(s->pool[i]);
     free(s);
 }
 
@@ -602,6 +604,20 @@ static void mom_offdiag(const ora_state* s, double* const phi[3], const double* 
     ora_lap(n, q, t_lap);
     for (size_t P = 0; P < s->N; ++P)
         out[P] += -(9.0 / 16.0) * divphi[P] * q[P] - mu * (t_lap[P] + 6.0 * q[P] / (h * h));
+}
+
+/* y = A x for the stacked momentum system: y_d = a_P x_d + N(x_d). */
+static void mom_apply(const ora_state* s, double* const fm[3], const double* divfm,
+                      const double* aP, double* const x[3], double* const y[3], double* t_face[3],
+                      double* t_lap) {
+    for (int d = 0; d < 3; ++d) {
+        mom_offdiag(s, fm, divfm, x[d], y[d], t_face, t_lap);
+        for (size_t P = 0; P < s->N; ++P) y[d][P] += aP[P] * x[d][P];
+    }
+}
+
+static double dot3(int n, double* const a[3], double* const b[3]) {
+    return dot_field(n, a[0], b[0]) + dot_field(n, a[1], b[1]) + dot_field(n, a[2], b[2]);
 }
 
 static void keep(double** slot, size_t N, const double* src) {
@@ -733,16 +749,70 @@ static int one_step(ora_state* s, ora_info* info) {
         unew[d] = pool_get(s, slot++);
         memcpy(ucur[d], s->u[d], N * sizeof(double));
     }
-    for (int sweep = 0; sweep < pr->n_mom_sweeps; ++sweep) {
+    if (pr->mom_tol > 0.0) {
+        /* BiCGStab on A u = s - grad p^n, right-preconditioned by K = diag(a_P) */
+        double *bv[3], *r[3], *rh[3], *p[3], *v[3], *y[3], *sv[3], *z[3], *t[3];
         for (int d = 0; d < 3; ++d) {
-            mom_offdiag(s, fm, divfm, ucur[d], noff, tface, tlap);
-            for (size_t P = 0; P < N; ++P)
-                unew[d][P] = (src[d][P] - noff[P] - gpn[d][P]) / aP[P];
+            bv[d] = pool_get(s, slot++); r[d] = pool_get(s, slot++); rh[d] = pool_get(s, slot++);
+            p[d] = pool_get(s, slot++); v[d] = pool_get(s, slot++); y[d] = pool_get(s, slot++);
+            sv[d] = pool_get(s, slot++); z[d] = pool_get(s, slot++); t[d] = pool_get(s, slot++);
+            for (size_t P = 0; P < N; ++P) bv[d][P] = src[d][P] - gpn[d][P];
         }
-        for (int d = 0; d < 3; ++d) {
-            double* tmp = ucur[d];
-            ucur[d] = unew[d];
-            unew[d] = tmp;
+        mom_apply(s, fm, divfm, aP, ucur, t, tface, tlap);
+        for (int d = 0; d < 3; ++d)
+            for (size_t P = 0; P < N; ++P) {
+                r[d][P] = bv[d][P] - t[d][P];
+                rh[d][P] = r[d][P];
+                p[d][P] = v[d][P] = 0.0;
+            }
+        const double bb = dot3(n, bv, bv), lim = pr->mom_tol * pr->mom_tol * bb;
+        double rr = dot3(n, r, r), rho_old = 1.0, alpha = 1.0, omega = 1.0;
+        int it = 0;
+        while (!(rr <= lim) && it < pr->mom_maxit) {
+            const double rho = dot3(n, rh, r);
+            const double beta = (rho / rho_old) * (alpha / omega);
+            for (int d = 0; d < 3; ++d)
+                for (size_t P = 0; P < N; ++P) {
+                    p[d][P] = r[d][P] + beta * (p[d][P] - omega * v[d][P]);
+                    y[d][P] = p[d][P] / aP[P];
+                }
+            mom_apply(s, fm, divfm, aP, y, v, tface, tlap);
+            alpha = rho / dot3(n, rh, v);
+            for (int d = 0; d < 3; ++d)
+                for (size_t P = 0; P < N; ++P) {
+                    sv[d][P] = r[d][P] - alpha * v[d][P];
+                    z[d][P] = sv[d][P] / aP[P];
+                }
+            mom_apply(s, fm, divfm, aP, z, t, tface, tlap);
+            const double tt = dot3(n, t, t);
+            omega = tt > 0.0 ? dot3(n, t, sv) / tt : 0.0;
+            for (int d = 0; d < 3; ++d)
+                for (size_t P = 0; P < N; ++P) {
+                    ucur[d][P] += alpha * y[d][P] + omega * z[d][P];
+                    r[d][P] = sv[d][P] - omega * t[d][P];
+                }
+            rho_old = rho;
+            rr = dot3(n, r, r);
+            ++it;
+        }
+        info->mom_iters = it;
+        info->mom_relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+        if (!(rr <= lim)) {
+            flags |= ORA_FLAG_MOM_MAXIT;
+            status = ORA_WARN_NOT_CONVERGED;
+        }
+    } else {
+        for (int sweep = 0; sweep < pr->n_mom_sweeps; ++sweep) {
+            for (int d = 0; d < 3; ++d) {
+                mom_offdiag(s, fm, divfm, ucur[d], noff, tface, tlap);
+                for (size_t P = 0; P < N; ++P)
+                    unew[d][P] = (src[d][P] - noff[P] - gpn[d][P]) / aP[P];
+            }
+            for (int d = 0; d < 3; ++d) {
+                double* tmp = ucur[d];
+                ucur[d] = unew[d];
+                unew[d] = tmp;
+            }
         }
     }
 

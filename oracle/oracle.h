@@ -49,6 +49,8 @@ extern "C" {
  * I4 transport symbol z) amplifies some Fourier mode beyond that (warning) */
 #define ORA_FLAG_DUST_COURANT 512
 #define ORA_DUST_COURANT_MAX 0.638
+/* the momentum predictor's BiCGStab reached mom_maxit before mom_tol (warning) */
+#define ORA_FLAG_MOM_MAXIT 1024
 
 typedef struct {
     int32_t n;
@@ -77,6 +79,13 @@ typedef struct {
      * with no previous one, is BDF1: w = 0).  BDF2 takes the barotropic,
      * one-way step only. */
     int32_t time_scheme;
+    /* momentum predictor: mom_tol = 0, n_mom_sweeps Jacobi sweeps; mom_tol > 0,
+     * the system a_P u + N(u) = s - grad p^n (the three components stacked)
+     * solved to ||r|| <= mom_tol ||s - grad p^n|| from u^n by BiCGStab
+     * (van der Vorst 1992) preconditioned with diag(a_P), at most mom_maxit
+     * iterations (not converged: ORA_FLAG_MOM_MAXIT, a warning) */
+    double mom_tol;
+    int32_t mom_maxit;
 } ora_params;
 
 #define ORA_BDF1 0
@@ -93,6 +102,8 @@ typedef struct {
     double mass_gas;
     double mass_p[ORA_MAX_CLASSES];
     double courant_dust;   /* max over the classes of sigma_j dt */
+    int32_t mom_iters;     /* BiCGStab iterations of the momentum predictor (mom_tol > 0) */
+    double mom_relres;     /* its final ||r|| / ||s - grad p^n|| */
 } ora_info;
 
 /* statistics, in this order */
