@@ -96,7 +96,10 @@ enum {
      * amplifies some Fourier mode beyond it.  The time step follows the gas's
      * Courant number only; the drift tau_j (g - Du/Dt) raises the dust's
      * (PISOC_WARN_DUST) */
-    PISOC_FLAG_DUST_COURANT = 512
+    PISOC_FLAG_DUST_COURANT = 512,
+    /* the momentum predictor's BiCGStab (mom_tol > 0) reached mom_maxit first
+     * (PISOC_WARN_NOT_CONVERGED) */
+    PISOC_FLAG_MOM_MAXIT = 1024
 };
 
 typedef struct {
@@ -166,6 +169,13 @@ typedef struct {
                                   defect, compressibility (c0 psi/dt) and density update,
                                   and the dust's acceleration and transport.  BDF2 needs
                                   FP64, the barotropic closure, two_way = 0 and one grid */
+    double mom_tol;            /* 0: the momentum predictor is n_mom_sweeps Jacobi sweeps (the
+                                  step above).  > 0 (FP64, one grid): the predictor's system
+                                  a_P u + N(u) = s - grad p^n, the three components stacked,
+                                  is solved from u^n to ||r|| <= mom_tol ||s - grad p^n|| by
+                                  BiCGStab (van der Vorst) preconditioned with diag(a_P);
+                                  reaching mom_maxit first raises PISOC_FLAG_MOM_MAXIT */
+    int32_t mom_maxit;
 } pisoc_params;
 
 enum { PISOC_BAROTROPIC = 0, PISOC_FOURIER = 1 };
@@ -182,6 +192,9 @@ typedef struct {
     double courant_dust;             /* max over the classes of sigma_j dt, sigma_j =
                                         max_P sum_f |G_f| / (2 rho^{n+1} V) with G the
                                         class's mass flux per unit mass ratio */
+    int32_t mom_iters;               /* BiCGStab iterations of the momentum predictor
+                                        (mom_tol > 0; else 0) */
+    double mom_relres;               /* its final ||r|| / ||s - grad p^n|| */
 } pisoc_step_info;
 
 typedef struct {

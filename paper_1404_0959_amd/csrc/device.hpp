@@ -74,6 +74,14 @@ struct PcgState {
     int32_t skip;     // 1: the refinement already meets the tolerance; later rounds do nothing
 };
 
+// State of the momentum predictor's BiCGStab (mom_tol > 0), on the device.
+struct BicgState {
+    double rho, rho_old, alpha, omega;  // (rh, r_k), (rh, r_{k-1}), alpha_k, omega_k
+    double bb, rr;                      // ||b||^2 and ||r||^2 of the last checked iterate
+    int32_t it_stop;                    // iteration count at the stop (kIterInf: running)
+    int32_t iters, converged, pad;
+};
+
 // Per-member device state, read back by the host after a batch of work.
 struct DevState {
     double dt, dt_prev, sigma, t;
@@ -108,6 +116,7 @@ struct DevState {
     double courant_dust;
     // BDF2 coefficients of the step (c0, c1, c2), written by the predictor
     double bdf[3];
+    BicgState bicg;
 };
 
 // A cell and the periodic offsets to the cells up to two steps away along

@@ -1770,6 +1770,187 @@ __global__ void __launch_bounds__(kBlock) k_energy_sweep(Phys ph, const DevState
     END_CELLS
 }
 
+// ---- the momentum predictor solved to a tolerance (BiCGStab) ----
+// A y = a_P y + N(y) for each velocity component, N the predictor's
+// off-diagonal part (I4 convection with the predictor's face fluxes F, less
+// its (9/16) div F diagonal; the compact viscous Laplacian without its centre):
+//   N(y)_P = (1/V) sum_f F_f^out I4(y)_f - (9/16) div(F) y_P - (mu/h^2) sum_nb y_nb.
+// b = s - grad p^n (Gauss-I4 gradient of the p^n field), the three components
+// stacked into one system; BiCGStab (van der Vorst) right-preconditioned by
+// K = diag(a_P), from x = u^n, to ||r|| <= mom_tol ||b||.  Per iteration i:
+// k_bicg_dir (test r_{i-1}; p = r + beta (p - omega v), v = A K^-1 p),
+// k_bicg_stab (s = r - alpha v, t = A K^-1 s) and k_bicg_update (x += alpha
+// K^-1 p + omega K^-1 s, r = s - omega t).  p and v alternate between two
+// buffers (the stencils read the previous ones at the neighbours).
+
+template <typename T, typename Y>
+__device__ inline double mom_op(const T* __restrict__ F, const T* __restrict__ aP, const CellIdx& c,
+                                size_t N, double inv_V, double mu_h2, Y&& y) {
+    const size_t P = c.self();
+    const double yP = y(P);
+    double conv = 0.0, dF = 0.0, nb = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double fp = (double)F[d * N + P], fm = (double)F[d * N + c.sh(d, -1)];
+        const double ym2 = y(c.sh(d, -2)), ym1 = y(c.sh(d, -1)), yp1 = y(c.sh(d, 1)),
+                     yp2 = y(c.sh(d, 2));
+        conv += fp * ((9.0 * (yP + yp1) - (ym1 + yp2)) * 0.0625) -
+                fm * ((9.0 * (ym1 + yP) - (ym2 + yp1)) * 0.0625);
+        dF += fp - fm;
+        nb += yp1 + ym1;
+    }
+    return (double)aP[P] * yP + conv * inv_V - 0.5625 * dF * inv_V * yP - mu_h2 * nb;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bicg_init(Phys ph, DevState* st, const T* __restrict__ x,
+                                                      const T* __restrict__ F, const T* __restrict__ aP,
+                                                      const T* __restrict__ src, const T* __restrict__ pn,
+                                                      T* __restrict__ r, T* __restrict__ rh,
+                                                      double* part) {
+    MEMBER(ph)
+    const size_t N = ncell(ph);
+    const double mu_h2 = ph.mu * ph.inv_h2;
+    double v[3] = {0.0, 0.0, 0.0};   // (rh, r) = (r, r), (r, r), (b, b)
+    FOR_CELLS(ph)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const T* xm = x + m * N;
+        const double b = (double)src[m * N + P] - (double)((i4(pn, c, m, 0) - i4(pn, c, m, -1)) * (T)ph.inv_h);
+        const double ax = mom_op(F, aP, c, N, ph.inv_V, mu_h2, [&](size_t Q) { return (double)xm[Q]; });
+        const double rr = b - ax;
+        r[m * N + P] = (T)rr;
+        rh[m * N + P] = (T)rr;
+        v[0] += rr * rr;
+        v[2] += b * b;
+    }
+    v[1] = v[0];
+    END_CELLS
+    block_partials<3, 0u>(v, part);
+    if (MEMBER_FIRST()) {
+        BicgState& g = (st + mem_)->bicg;
+        g.it_stop = kIterInf;
+        g.iters = 0;
+        g.converged = 0;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bicg_dir(Phys ph, DevState* st, int i, double tol2, int maxit,
+                                                     const T* __restrict__ r, const T* __restrict__ rh,
+                                                     const T* __restrict__ pold, const T* __restrict__ vold,
+                                                     T* __restrict__ pnew, T* __restrict__ vnew,
+                                                     const T* __restrict__ F, const T* __restrict__ aP,
+                                                     const double* part_res, double* part_v) {
+    MEMBER(ph)
+    BicgState& g = (st + mem_)->bicg;
+    if (i - 1 > g.it_stop) return;
+    const size_t N = ncell(ph);
+    double t[3];
+    reduce_member<3, 0u>(part_res, num_blocks(), ph.batch, mem_, t);
+    const double rho = t[0], rr = t[1], bb = i == 1 ? t[2] : g.bb;
+    const bool conv = rr <= tol2 * bb;
+    const bool stop = conv || i - 1 >= maxit;
+    if (MEMBER_FIRST()) {
+        if (i == 1) g.bb = bb;
+        g.rr = rr;
+        g.rho = rho;
+        if (stop) {
+            g.it_stop = i - 1;
+            g.iters = i - 1;
+            g.converged = conv ? 1 : 0;
+            if (!conv) (st + mem_)->flags |= 1024;   // the cap reached first
+        }
+    }
+    if (stop) return;
+    const double beta = i == 1 ? 0.0 : (rho / g.rho_old) * (g.alpha / g.omega);
+    const double om = i == 1 ? 0.0 : g.omega;
+    const double mu_h2 = ph.mu * ph.inv_h2;
+    double v[1] = {0.0};
+    FOR_CELLS(ph)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const size_t o = m * N;
+        auto pv = [&](size_t Q) -> double {
+            return i == 1 ? (double)r[o + Q]
+                          : (double)r[o + Q] + beta * ((double)pold[o + Q] - om * (double)vold[o + Q]);
+        };
+        const double av = mom_op(F, aP, c, N, ph.inv_V, mu_h2, [&](size_t Q) { return pv(Q) / (double)aP[Q]; });
+        pnew[o + P] = (T)pv(P);
+        vnew[o + P] = (T)av;
+        v[0] += (double)rh[o + P] * av;
+    }
+    END_CELLS
+    block_partials<1, 0u>(v, part_v);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bicg_stab(Phys ph, DevState* st, int i,
+                                                      const T* __restrict__ r, const T* __restrict__ vv,
+                                                      T* __restrict__ s, T* __restrict__ tt,
+                                                      const T* __restrict__ F, const T* __restrict__ aP,
+                                                      const double* part_v, double* part_ts) {
+    MEMBER(ph)
+    BicgState& g = (st + mem_)->bicg;
+    if (i - 1 >= g.it_stop) return;
+    const size_t N = ncell(ph);
+    double rv[1];
+    reduce_member<1, 0u>(part_v, num_blocks(), ph.batch, mem_, rv);
+    const double alpha = g.rho / rv[0];
+    if (MEMBER_FIRST()) g.alpha = alpha;
+    const double mu_h2 = ph.mu * ph.inv_h2;
+    double v[2] = {0.0, 0.0};
+    FOR_CELLS(ph)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const size_t o = m * N;
+        auto sv = [&](size_t Q) -> double { return (double)r[o + Q] - alpha * (double)vv[o + Q]; };
+        const double at = mom_op(F, aP, c, N, ph.inv_V, mu_h2, [&](size_t Q) { return sv(Q) / (double)aP[Q]; });
+        const double sP = sv(P);
+        s[o + P] = (T)sP;
+        tt[o + P] = (T)at;
+        v[0] += at * sP;
+        v[1] += at * at;
+    }
+    END_CELLS
+    block_partials<2, 0u>(v, part_ts);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bicg_update(Phys ph, DevState* st, int i, T* __restrict__ x,
+                                                        const T* __restrict__ p, const T* __restrict__ s,
+                                                        const T* __restrict__ tt, T* __restrict__ r,
+                                                        const T* __restrict__ rh, const T* __restrict__ aP,
+                                                        const double* part_ts, double* part_res) {
+    MEMBER(ph)
+    BicgState& g = (st + mem_)->bicg;
+    if (i - 1 >= g.it_stop) return;
+    const size_t N = ncell(ph);
+    double ts[2];
+    reduce_member<2, 0u>(part_ts, num_blocks(), ph.batch, mem_, ts);
+    const double omega = ts[1] > 0.0 ? ts[0] / ts[1] : 0.0;
+    const double alpha = g.alpha;
+    if (MEMBER_FIRST()) {
+        g.omega = omega;
+        g.rho_old = g.rho;
+    }
+    double v[2] = {0.0, 0.0};
+    FOR_CELLS(ph)
+    const double ia = 1.0 / (double)aP[P];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const size_t o = m * N + P;
+        const double sP = (double)s[o];
+        x[o] = (T)((double)x[o] + alpha * ((double)p[o] * ia) + omega * (sP * ia));
+        const double rn = sP - omega * (double)tt[o];
+        r[o] = (T)rn;
+        v[0] += (double)rh[o] * rn;
+        v[1] += rn * rn;
+    }
+    END_CELLS
+    block_partials<2, 0u>(v, part_res);
+}
+
 // y = M x for the stand-alone operator entry point (psi/dt given as a field).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_helm_apply(Phys ph, const T* __restrict__ psidt,
@@ -3464,6 +3645,25 @@ template <typename T>
 void Ops<T>::helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt, const T* w,
                         const T* x, T* y) {
     LAUNCH(k_helm_apply<T>, L, s, ph, psidt, w, x, y);
+}
+template <typename T>
+void Ops<T>::bicg_init(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, const T* x,
+                       const T* F, const T* aP, const T* src, const T* pn, T* r, T* rh, double* part) {
+    LAUNCH(k_bicg_init<T>, L, s, ph, st, x, F, aP, src, pn, r, rh, part);
+}
+template <typename T>
+void Ops<T>::bicg_iter(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int i,
+                       double tol2, int maxit, T* x, T* r, const T* rh, T* const p[2], T* const v[2],
+                       T* sv, T* tv, const T* F, const T* aP, double* part_res, double* part_v,
+                       double* part_ts) {
+    T* pold = p[(i + 1) & 1];
+    T* vold = v[(i + 1) & 1];
+    T* pnew = p[i & 1];
+    T* vnew = v[i & 1];
+    LAUNCH(k_bicg_dir<T>, L, s, ph, st, i, tol2, maxit, r, rh, pold, vold, pnew, vnew, F, aP, part_res,
+           part_v);
+    LAUNCH(k_bicg_stab<T>, L, s, ph, st, i, r, vnew, sv, tv, F, aP, part_v, part_ts);
+    LAUNCH(k_bicg_update<T>, L, s, ph, st, i, x, pnew, sv, tv, r, rh, aP, part_ts, part_res);
 }
 template <typename T>
 void Ops<T>::energy_setup(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,

@@ -60,6 +60,9 @@ void psidt_of(hipStream_t s, int n, const double* diag, const double* w, double*
 
 // Partial-sum columns written by one CG iteration.
 constexpr int kCgCols = 7;
+// The momentum predictor's BiCGStab: partial slots from PS_CG for (rh.r, r.r,
+// b.b), (rh.v) and (t.s, t.t).
+constexpr int kBicgRes = 0, kBicgV = 3, kBicgTs = 4;
 // Chebyshev-preconditioned CG: one set of columns per iteration (r.z, r.r,
 // p.q), sets alternating by k & 1 from PS_CG, the interval's end after them.
 constexpr int kChebRes = 0, kChebDir = 2, kChebSet = 3;
@@ -153,6 +156,15 @@ struct Ops {
                          DevState* st, int k, const CgArgs<T>& a);
     static void helm_apply(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt,
                            const T* w, const T* x, T* y);
+    // the momentum predictor solved to a tolerance: BiCGStab set-up (x = u^n
+    // in place) and iteration i >= 1 (three launches)
+    static void bicg_init(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, const T* x,
+                          const T* F, const T* aP, const T* src, const T* pn, T* r, T* rh,
+                          double* part);
+    static void bicg_iter(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int i,
+                          double tol2, int maxit, T* x, T* r, const T* rh, T* const p[2],
+                          T* const v[2], T* sv, T* tv, const T* F, const T* aP, double* part_res,
+                          double* part_v, double* part_ts);
     // Fourier closure: the energy predictor's coefficients and one Jacobi sweep
     static void energy_setup(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                              const T* rn, const T* rs, const T* phi, const T* divu, const T* pn,

@@ -75,6 +75,7 @@ struct Layout {
     size_t xprev;  // previous-step guess: each corrector's last solution
     size_t t0, t1, tw, eaT, esT;  // Fourier closure: T (two rotating), sweep scratch, a_T, s_T
     size_t rm1, um1, rjm1;        // BDF2: rho, u, rho_j at t^{n-1}
+    size_t bicg;                  // momentum BiCGStab: r, rh, p x2, v x2, s, t (3 N each)
     size_t total;
     unsigned max_blocks;     // column length of the partials (all members)
 };
@@ -186,6 +187,9 @@ bool valid_params(const pisoc_params* p, std::string* why) {
         if (!std::isfinite(p->gravity[d])) return fail("gravity must be finite");
     if (p->closure != PISOC_BAROTROPIC && p->closure != PISOC_FOURIER) return fail("unknown closure");
     if (p->time_scheme != PISOC_BDF1 && p->time_scheme != PISOC_BDF2) return fail("unknown time scheme");
+    if (!(p->mom_tol >= 0.0) || !(p->mom_tol < 1.0)) return fail("mom_tol must be in [0, 1)");
+    if (p->mom_tol > 0.0 && (p->mom_maxit < 1 || p->precision != PISOC_FP64))
+        return fail("a tolerance-solved momentum predictor needs mom_maxit >= 1 and FP64");
     if (p->time_scheme == PISOC_BDF2 &&
         (p->precision != PISOC_FP64 || p->closure != PISOC_BAROTROPIC || p->two_way))
         return fail("BDF2 needs FP64, the barotropic closure and two_way = 0");
@@ -230,6 +234,7 @@ Layout make_layout(const pisoc_params* p, int batch) {
     }
     L.snap = p->capture ? take((p->guess != PISOC_GUESS_ZERO ? 10 : 8) * sizeof(double) * N)
                         : 0;
+    if (p->mom_tol > 0.0) L.bicg = take(8 * 3 * es * N);
     if (p->time_scheme == PISOC_BDF2) {   // FP64 only
         L.rm1 = take(sizeof(double) * N);
         L.um1 = take(3 * sizeof(double) * N);
@@ -625,7 +630,7 @@ CgVecs<T> cg_vecs(const StepPtrs<T>& S) {
 // the u slot ctx->ucur_slot).
 // cfl_ready: the Courant partials of the current state are already in PS_CFL.
 template <typename T>
-void enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
+pisoc_status enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
     using O = Ops<T>;
     const pisoc_params& p = ctx->prm;
     const Phys& ph = ctx->ph;
@@ -653,11 +658,43 @@ void enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
         });
     }
     T* uin = S.un;
-    for (int i = 0; i < p.n_mom_sweeps; ++i) {
-        T* uout = (i & 1) ? S.ub : S.ua;
-        timed(ctx, KC_MOM_SWEEP, 14, -1,
-              [&] { O::mom_sweep(L, ctx->TL, s, ph, st, uin, uout, S.mflux, S.aP, S.src, S.pn); });
-        uin = uout;
+    if (p.mom_tol > 0.0) {
+        // BiCGStab from u^n, in place in the u* slot; batches of 8 iterations
+        // with a host wait after each until the solve has stopped
+        T* x = ucur_of(ctx, S);
+        T* w = ctx->f<T>(ctx->lay.bicg);
+        const size_t n3 = 3 * ctx->NT();
+        T* r = w;
+        T* rh = w + n3;
+        T* const pp[2] = {w + 2 * n3, w + 3 * n3};
+        T* const vv[2] = {w + 4 * n3, w + 5 * n3};
+        T* sv = w + 6 * n3;
+        T* tv = w + 7 * n3;
+        if (hipMemcpyAsync(x, S.un, n3 * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            ctx->err = "hipMemcpyAsync failed";
+            return PISOC_ERR_HIP;
+        }
+        double* pres = ctx->part(PS_CG + kBicgRes);
+        O::bicg_init(L, s, ph, st, x, S.mflux, S.aP, S.src, S.pn, r, rh, pres);
+        const double tol2 = p.mom_tol * p.mom_tol;
+        for (int i = 1;; i += 8) {
+            for (int k = i; k < i + 8; ++k)
+                O::bicg_iter(L, s, ph, st, k, tol2, p.mom_maxit, x, r, rh, pp, vv, sv, tv, S.mflux,
+                             S.aP, pres, ctx->part(PS_CG + kBicgV), ctx->part(PS_CG + kBicgTs));
+            pisoc_status ss = sync_state(ctx);
+            if (ss != PISOC_OK) return ss;
+            bool all = true;
+            for (int m = 0; m < ctx->batch; ++m) all = all && ctx->hst[m].bicg.it_stop != kIterInf;
+            if (all) break;
+        }
+        uin = x;
+    } else {
+        for (int i = 0; i < p.n_mom_sweeps; ++i) {
+            T* uout = (i & 1) ? S.ub : S.ua;
+            timed(ctx, KC_MOM_SWEEP, 14, -1,
+                  [&] { O::mom_sweep(L, ctx->TL, s, ph, st, uin, uout, S.mflux, S.aP, S.src, S.pn); });
+            uin = uout;
+        }
     }
     if (S.snap)   // the predictor's output u*
         for (int d = 0; d < 3; ++d)
@@ -676,6 +713,7 @@ void enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
             tin = tout;
         }
     }
+    return PISOC_OK;
 }
 
 template <typename T>
@@ -1025,7 +1063,7 @@ pisoc_status enqueue_step(pisoc_ctx* ctx, bool eager) {
         ctx->ph.um1 = ctx->f<double>(ctx->um1);
         ctx->ph.rjm1 = ctx->f<double>(ctx->rjm1);
     }
-    enqueue_front<T>(ctx, S, cfl_ready);
+    if (pisoc_status fs = enqueue_front<T>(ctx, S, cfl_ready); fs != PISOC_OK) return fs;
     // with the audit on, an eager step takes this step's decision and a
     // captured one the verdict it was built with (audit_decide_capture)
     const bool audit = eager && audit_on(ctx);
@@ -1123,6 +1161,8 @@ void fill_info(const pisoc_ctx* ctx, const DevState& h, bool committed, pisoc_st
     }
     for (int c = 0; c < ctx->prm.n_classes; ++c) rec.mass_p[c] = h.mass_p[c];
     rec.courant_dust = h.courant_dust;
+    rec.mom_iters = h.bicg.iters;
+    rec.mom_relres = h.bicg.bb > 0.0 ? std::sqrt(h.bicg.rr / h.bicg.bb) : 0.0;
     *out = rec;
 }
 
@@ -1135,7 +1175,7 @@ bool member_bad(const pisoc_ctx* ctx, const DevState& h) {
 }
 
 pisoc_status flag_status(int flags) {
-    if (flags & PISOC_FLAG_PCG_MAXIT) return PISOC_WARN_NOT_CONVERGED;
+    if (flags & (PISOC_FLAG_PCG_MAXIT | PISOC_FLAG_MOM_MAXIT)) return PISOC_WARN_NOT_CONVERGED;
     if (flags & (PISOC_FLAG_DUST_NEG | PISOC_FLAG_DUST_DIAG | PISOC_FLAG_DUST_COURANT))
         return PISOC_WARN_DUST;
     if (flags & PISOC_FLAG_GUESS_FALLBACK) return PISOC_WARN_GUESS_FALLBACK;
@@ -1986,8 +2026,10 @@ bool ens_classes(const pisoc_params* members, int32_t count, std::vector<std::ve
     }
     for (int m = 0; m < count; ++m) {
         if (!valid_params(&members[m], why)) return false;
-        if (members[m].closure != PISOC_BAROTROPIC || members[m].time_scheme != PISOC_BDF1) {
-            if (why) *why = "ensembles take the barotropic closure and backward Euler only";
+        if (members[m].closure != PISOC_BAROTROPIC || members[m].time_scheme != PISOC_BDF1 ||
+            members[m].mom_tol > 0.0) {
+            if (why) *why = "ensembles take the barotropic closure, backward Euler and the "
+                            "swept momentum predictor only";
             return false;
         }
         if (!same_class_params(members[m], members[0])) {

@@ -23,6 +23,7 @@ GUESS_ZERO, GUESS_LEARNED, GUESS_PREVIOUS = 0, 1, 2
 FLAG_PCG_MAXIT, FLAG_NONFINITE, FLAG_RHO_NONPOS, FLAG_GUESS_FALLBACK, FLAG_BAD_DT = 1, 2, 4, 8, 16
 FLAG_GUESS_SKIPPED = 32
 FLAG_DUST_NEG, FLAG_DUST_NONFINITE, FLAG_DUST_DIAG, FLAG_DUST_COURANT = 64, 128, 256, 512
+FLAG_MOM_MAXIT = 1024
 
 FIELD_RHO, FIELD_U, FIELD_PHI, FIELD_RHO_P, FIELD_P = 1, 2, 4, 8, 16
 FIELD_PSOLVE_B, FIELD_PSOLVE_X, FIELD_P_PREV, FIELD_PSOLVE_DIAG = 32, 64, 128, 256
@@ -70,6 +71,7 @@ class Params(C.Structure):
         ("two_way", C.c_int32), ("gravity", C.c_double * 3),
         ("closure", C.c_int32), ("R_gas", C.c_double), ("cv", C.c_double),
         ("kappa", C.c_double), ("T0", C.c_double), ("time_scheme", C.c_int32),
+        ("mom_tol", C.c_double), ("mom_maxit", C.c_int32),
     ]
 
 
@@ -80,6 +82,7 @@ class StepInfo(C.Structure):
         ("refinements", C.c_int32 * MAX_CORR),
         ("flags", C.c_int32), ("mass_gas", C.c_double),
         ("mass_p", C.c_double * MAX_CLASSES), ("courant_dust", C.c_double),
+        ("mom_iters", C.c_int32), ("mom_relres", C.c_double),
     ]
 
 
@@ -232,7 +235,8 @@ def make_params(n, *, gamma, C_, mu, tau_p=(), cfl=0.5, dt_growth=1.2, dt_fixed=
                 n_corr=2, n_mom_sweeps=4, n_dust_sweeps=4, p_tol=1e-8, p_maxit=500,
                 precision=FP64, guess=GUESS_ZERO, guess_weights=None, inner_tol=1e-7,
                 max_refine=20, capture=False, guess_audit=0, two_way=False,
-                gravity=(0.0, 0.0, 0.0), fourier=None, bdf2=False) -> Params:
+                gravity=(0.0, 0.0, 0.0), fourier=None, bdf2=False, mom_tol=0.0,
+                mom_maxit=200) -> Params:
     """fourier: None (barotropic) or dict(R=, cv=, kappa=, T0=) for the ideal gas
     with the energy equation; bdf2: the variable-step BDF2 time scheme."""
     p = Params()
@@ -256,6 +260,7 @@ def make_params(n, *, gamma, C_, mu, tau_p=(), cfl=0.5, dt_growth=1.2, dt_fixed=
         p.closure = FOURIER
         p.R_gas, p.cv, p.kappa, p.T0 = fourier["R"], fourier["cv"], fourier["kappa"], fourier["T0"]
     p.time_scheme = BDF2 if bdf2 else BDF1
+    p.mom_tol, p.mom_maxit = mom_tol, mom_maxit
     return p
 
 
@@ -381,7 +386,7 @@ def _info_dict(r, nc, K):
     return dict(t=r.t, dt=r.dt, courant=r.courant, pcg_iters=list(r.pcg_iters[:nc]),
                 pcg_relres=list(r.pcg_relres[:nc]), refinements=list(r.refinements[:nc]),
                 flags=r.flags, mass_gas=r.mass_gas, mass_p=list(r.mass_p[:K]),
-                courant_dust=r.courant_dust)
+                courant_dust=r.courant_dust, mom_iters=r.mom_iters, mom_relres=r.mom_relres)
 
 
 class Ensemble:

@@ -98,6 +98,21 @@ def test_bdf2_params_rejected(lib, change):
     assert lib.pisoc_workspace_bytes(ctypes.byref(p)) == 0
 
 
+@pytest.mark.parametrize("change", [
+    dict(mom_tol=-1e-6), dict(mom_tol=1.0), dict(mom_maxit=0),
+    dict(precision=P.FP32_REFINED, inner_tol=1e-6),
+])
+def test_mom_tol_params_rejected(lib, change):
+    """The tolerance-solved momentum predictor: 0 < mom_tol < 1, mom_maxit >= 1,
+    FP64, single grids."""
+    p = P.make_params(32, gamma=1.4, C_=53.6, mu=1e-3, tau_p=(0.01,), mom_tol=1e-8)
+    assert lib.pisoc_workspace_bytes(ctypes.byref(p)) > 0
+    assert lib.pisoc_ens_workspace_bytes(ctypes.byref(p), 1) == 0
+    for k, v in change.items():
+        setattr(p, k, v)
+    assert lib.pisoc_workspace_bytes(ctypes.byref(p)) == 0
+
+
 def test_fourier_workspace_and_ensemble_rejection(lib):
     """The closure adds five FP64 cell fields; an ensemble member with it is
     rejected."""

@@ -1,0 +1,76 @@
+"""The momentum predictor solved to a tolerance by BiCGStab on the GPU
+(gathered FP64 kernels) against the oracle's: the predictor's output u*, the
+whole step's fields and the iteration counts of both solvers; the shear-wave
+one-iteration case and the cap."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1404_0959_amd.inputs import make_hit_case
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1404_0959_amd.pisoc as P
+    P.lib()
+    return P
+
+
+def err(g, o):
+    g, o = np.asarray(g), np.asarray(o)
+    d = float(np.max(np.abs(g - o)))
+    spread = float(np.max(np.abs(o - o.mean())))
+    mag = float(np.max(np.abs(o)))
+    return (d / spread if spread > 0 else (0.0 if d == 0 else np.inf),
+            d / mag if mag > 0 else (0.0 if d == 0 else np.inf))
+
+
+@pytest.mark.parametrize("n,steps,tol", [(16, 4, 1e-10), (32, 3, 1e-8), (40, 2, 1e-10)])
+def test_bicgstab_step_parity(P, ora, n, steps, tol):
+    case = make_hit_case(n, 31, mach=0.3, stokes=(0.1,))
+    o = ora.Oracle.from_case(case, p_tol=1e-10, mom_tol=tol, capture=True)
+    s = P.Solver.from_case(case, p_tol=1e-10, mom_tol=tol, capture=True)
+    for k in range(steps):
+        so, io = o.step(1)
+        sg, ig = s.step(1)
+        assert so == sg, (k, so, sg)
+        print(f"{n}^3 step {k}: BiCGStab iterations GPU {ig[0]['mom_iters']} oracle "
+              f"{io[0]['mom_iters']}, relres {ig[0]['mom_relres']:.2e}")
+        assert ig[0]["mom_iters"] == io[0]["mom_iters"] and ig[0]["mom_iters"] > 1
+        assert abs(ig[0]["mom_relres"] / io[0]["mom_relres"] - 1) <= 1e-3
+        assert ig[0]["pcg_iters"] == io[0]["pcg_iters"]
+    f = s.fields(P.FIELD_USTAR | P.FIELD_RHO | P.FIELD_U | P.FIELD_RHO_P)
+    for fb, ob in ((P.FIELD_USTAR, ora.SYS_USTAR), (P.FIELD_RHO, ora.RHO), (P.FIELD_U, ora.U),
+                   (P.FIELD_RHO_P, ora.RHO_P)):
+        r_dev, r_mag = err(f[fb].cpu().numpy(), o.get(ob))
+        print(f"{n}^3 BiCGStab predictor, field {fb}: dev {r_dev:.2e} mag {r_mag:.2e}")
+        assert r_mag <= TOL and r_dev <= TOL, fb
+
+
+def test_bicgstab_shear_wave_and_cap(P):
+    n, mu, dt = 16, 0.05, 0.05
+    h = 2 * math.pi / n
+    y = (np.arange(n) + 0.5) * h
+    u = np.zeros((3, n, n, n))
+    u[0] = 0.01 * np.sin(y)[None, :, None]
+    s = P.Solver(n, np.ones((n, n, n)), u, gamma=1.4, C_=1e4, mu=mu, dt_fixed=dt, p_tol=1e-12,
+                 mom_tol=1e-13, capture=True)
+    st, info = s.step(1)
+    assert st == P.OK and info[0]["mom_iters"] == 1
+    lam = (2 - 2 * math.cos(h)) / h ** 2
+    want = 0.01 * np.sin(y) / (1 + dt * mu * lam)
+    ux = s.get(P.FIELD_USTAR).cpu().numpy()[0]
+    assert np.max(np.abs(ux - want[None, :, None])) <= 1e-15
+    case = make_hit_case(16, 10, mach=0.3, stokes=(0.1,))
+    s = P.Solver.from_case(case, p_tol=1e-10, mom_tol=1e-14, mom_maxit=1)
+    st, info = s.step(1)
+    assert st == P.WARN_NOT_CONVERGED and info[0]["flags"] & P.FLAG_MOM_MAXIT
+    assert info[0]["mom_iters"] == 1
