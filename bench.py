@@ -204,8 +204,10 @@ def ensemble_run(P, torch, args, weights):
 def extras_run(P, torch, case, args):
     """The other rows of the step at the benchmark's size: the two-way coupled
     mixture with gravity settling (FP32 refined, same workload, dust loading
-    raised to 0.2), and the flow diagnostics on the velocity field, each with
-    its algorithmic bytes (words each kernel must read or write once)."""
+    raised to 0.2), the FP64 variants (Fourier closure, BDF2, momentum
+    predictor solved by BiCGStab), the flow diagnostics on the velocity field,
+    each with its algorithmic bytes (words each kernel must read or write
+    once), and the guess network alone."""
     import numpy as np
     out = {}
     n3 = args.n ** 3
@@ -227,6 +229,30 @@ def extras_run(P, torch, case, args):
     u = s.get(P.FIELD_U)
     s.close()
     del s
+    # variants of the FP64 step, all on the gathered field kernels: the Fourier
+    # closure (ideal gas with R = 1, c_v = 2.5, so c_p/c_v = 1.4, T0 = C so
+    # that the sound speed matches the barotropic gas), BDF2, and the momentum
+    # predictor solved to 1e-8 by BiCGStab
+    fz = dict(R=1.0, cv=2.5, kappa=1e-3, T0=case.C)
+    base = dict(p_tol=args.p_tol, cfl=0.5, n_corr=2, n_mom_sweeps=4, n_dust_sweeps=4)
+    for name, extra in (("fourier_fp64", dict(fourier=fz)), ("bdf2_fp64", dict(bdf2=True)),
+                        ("mom_bicgstab_fp64", dict(mom_tol=1e-8))):
+        s = P.Solver(case.n, case.rho, case.u, case.rho_p, gamma=case.gamma, C_=case.C,
+                     mu=case.mu, tau_p=case.tau_p, **base, **extra)
+        s.step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = s.step(args.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = dict(value=n3 * args.steps / el, unit="cell-steps/s",
+                         ms_per_step=el * 1e3 / args.steps, status=st,
+                         pcg_iters_mean=float(np.mean([np.mean(i["pcg_iters"]) for i in info])))
+        if "mom_tol" in extra:
+            out[name]["mom_iters_mean"] = float(np.mean([i["mom_iters"] for i in info]))
+        log(f"{name}: {el * 1e3 / args.steps:.3f} ms/step")
+        s.close()
+        del s
 
     def time_it(fn, reps=5):
         fn()
