@@ -1777,23 +1777,24 @@ __global__ void __launch_bounds__(kBlock) k_energy_sweep(Phys ph, const DevState
 //   N(y)_P = (1/V) sum_f F_f^out I4(y)_f - (9/16) div(F) y_P - (mu/h^2) sum_nb y_nb.
 // b = s - grad p^n (Gauss-I4 gradient of the p^n field), the three components
 // stacked into one system; BiCGStab (van der Vorst) right-preconditioned by
-// K = diag(a_P), from x = u^n, to ||r|| <= mom_tol ||b||.  Per iteration i:
-// k_bicg_dir (test r_{i-1}; p = r + beta (p - omega v), v = A K^-1 p),
-// k_bicg_stab (s = r - alpha v, t = A K^-1 s) and k_bicg_update (x += alpha
-// K^-1 p + omega K^-1 s, r = s - omega t).  p and v alternate between two
-// buffers (the stencils read the previous ones at the neighbours).
-
-template <typename T, typename Y>
-__device__ inline double mom_op(const T* __restrict__ F, const T* __restrict__ aP, const CellIdx& c,
-                                size_t N, double inv_V, double mu_h2, Y&& y) {
+// K = diag(a_P), from x = u^n, to ||r|| <= mom_tol ||b||.  Per iteration i,
+// five launches: k_bicg_dir tests r_{i-1} and forms p = r + beta (p - omega v)
+// and y = K^-1 p on the cell; k_bicg_apply takes v = A y on the stencil;
+// k_bicg_half forms s = r - alpha v and z = K^-1 s; k_bicg_apply again takes
+// t = A z; k_bicg_update forms x += alpha y + omega z and r = s - omega t.
+// The pointwise launches let the stencil ones read one stored field.
+template <typename T>
+__device__ inline double mom_op(const T* __restrict__ F, const T* __restrict__ aP,
+                                const T* __restrict__ y, const CellIdx& c, size_t N, double inv_V,
+                                double mu_h2) {
     const size_t P = c.self();
-    const double yP = y(P);
+    const double yP = (double)y[P];
     double conv = 0.0, dF = 0.0, nb = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double fp = (double)F[d * N + P], fm = (double)F[d * N + c.sh(d, -1)];
-        const double ym2 = y(c.sh(d, -2)), ym1 = y(c.sh(d, -1)), yp1 = y(c.sh(d, 1)),
-                     yp2 = y(c.sh(d, 2));
+        const double ym2 = (double)y[c.sh(d, -2)], ym1 = (double)y[c.sh(d, -1)],
+                     yp1 = (double)y[c.sh(d, 1)], yp2 = (double)y[c.sh(d, 2)];
         conv += fp * ((9.0 * (yP + yp1) - (ym1 + yp2)) * 0.0625) -
                 fm * ((9.0 * (ym1 + yP) - (ym2 + yp1)) * 0.0625);
         dF += fp - fm;
@@ -1815,9 +1816,8 @@ __global__ void __launch_bounds__(kBlock) k_bicg_init(Phys ph, DevState* st, con
     FOR_CELLS(ph)
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        const T* xm = x + m * N;
         const double b = (double)src[m * N + P] - (double)((i4(pn, c, m, 0) - i4(pn, c, m, -1)) * (T)ph.inv_h);
-        const double ax = mom_op(F, aP, c, N, ph.inv_V, mu_h2, [&](size_t Q) { return (double)xm[Q]; });
+        const double ax = mom_op(F, aP, x + m * N, c, N, ph.inv_V, mu_h2);
         const double rr = b - ax;
         r[m * N + P] = (T)rr;
         rh[m * N + P] = (T)rr;
@@ -1835,13 +1835,12 @@ __global__ void __launch_bounds__(kBlock) k_bicg_init(Phys ph, DevState* st, con
     }
 }
 
+// Test r_{i-1}; p = r + beta (p - omega v), y = p / a_P (on the cell).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_bicg_dir(Phys ph, DevState* st, int i, double tol2, int maxit,
-                                                     const T* __restrict__ r, const T* __restrict__ rh,
-                                                     const T* __restrict__ pold, const T* __restrict__ vold,
-                                                     T* __restrict__ pnew, T* __restrict__ vnew,
-                                                     const T* __restrict__ F, const T* __restrict__ aP,
-                                                     const double* part_res, double* part_v) {
+                                                     const T* __restrict__ r, T* __restrict__ p,
+                                                     const T* __restrict__ vv, T* __restrict__ y,
+                                                     const T* __restrict__ aP, const double* part_res) {
     MEMBER(ph)
     BicgState& g = (st + mem_)->bicg;
     if (i - 1 > g.it_stop) return;
@@ -1865,31 +1864,53 @@ __global__ void __launch_bounds__(kBlock) k_bicg_dir(Phys ph, DevState* st, int 
     if (stop) return;
     const double beta = i == 1 ? 0.0 : (rho / g.rho_old) * (g.alpha / g.omega);
     const double om = i == 1 ? 0.0 : g.omega;
+    FOR_CELLS(ph)
+    const double ia = 1.0 / (double)aP[P];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const size_t o = m * N + P;
+        const double pv = i == 1 ? (double)r[o] : (double)r[o] + beta * ((double)p[o] - om * (double)vv[o]);
+        p[o] = (T)pv;
+        y[o] = (T)(pv * ia);
+    }
+    END_CELLS
+}
+
+// out = A y for the three components; partials (w, out) and, with w2, (out, out).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bicg_apply(Phys ph, DevState* st, int i, int after_half,
+                                                       const T* __restrict__ y, T* __restrict__ out,
+                                                       const T* __restrict__ F, const T* __restrict__ aP,
+                                                       const T* __restrict__ w, double* part) {
+    MEMBER(ph)
+    const BicgState& g = (st + mem_)->bicg;
+    if (i - 1 >= g.it_stop) return;
+    const size_t N = ncell(ph);
     const double mu_h2 = ph.mu * ph.inv_h2;
-    double v[1] = {0.0};
+    double v[2] = {0.0, 0.0};
     FOR_CELLS(ph)
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        const size_t o = m * N;
-        auto pv = [&](size_t Q) -> double {
-            return i == 1 ? (double)r[o + Q]
-                          : (double)r[o + Q] + beta * ((double)pold[o + Q] - om * (double)vold[o + Q]);
-        };
-        const double av = mom_op(F, aP, c, N, ph.inv_V, mu_h2, [&](size_t Q) { return pv(Q) / (double)aP[Q]; });
-        pnew[o + P] = (T)pv(P);
-        vnew[o + P] = (T)av;
-        v[0] += (double)rh[o + P] * av;
+        const double a = mom_op(F, aP, y + m * N, c, N, ph.inv_V, mu_h2);
+        out[m * N + P] = (T)a;
+        v[0] += (double)w[m * N + P] * a;
+        v[1] += a * a;
     }
     END_CELLS
-    block_partials<1, 0u>(v, part_v);
+    if (after_half) {
+        block_partials<2, 0u>(v, part);
+    } else {
+        double v1[1] = {v[0]};
+        block_partials<1, 0u>(v1, part);
+    }
 }
 
+// alpha = rho / (rh, v); s = r - alpha v, z = s / a_P (on the cell).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_bicg_stab(Phys ph, DevState* st, int i,
+__global__ void __launch_bounds__(kBlock) k_bicg_half(Phys ph, DevState* st, int i,
                                                       const T* __restrict__ r, const T* __restrict__ vv,
-                                                      T* __restrict__ s, T* __restrict__ tt,
-                                                      const T* __restrict__ F, const T* __restrict__ aP,
-                                                      const double* part_v, double* part_ts) {
+                                                      T* __restrict__ s, T* __restrict__ z,
+                                                      const T* __restrict__ aP, const double* part_v) {
     MEMBER(ph)
     BicgState& g = (st + mem_)->bicg;
     if (i - 1 >= g.it_stop) return;
@@ -1898,29 +1919,24 @@ __global__ void __launch_bounds__(kBlock) k_bicg_stab(Phys ph, DevState* st, int
     reduce_member<1, 0u>(part_v, num_blocks(), ph.batch, mem_, rv);
     const double alpha = g.rho / rv[0];
     if (MEMBER_FIRST()) g.alpha = alpha;
-    const double mu_h2 = ph.mu * ph.inv_h2;
-    double v[2] = {0.0, 0.0};
     FOR_CELLS(ph)
+    const double ia = 1.0 / (double)aP[P];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        const size_t o = m * N;
-        auto sv = [&](size_t Q) -> double { return (double)r[o + Q] - alpha * (double)vv[o + Q]; };
-        const double at = mom_op(F, aP, c, N, ph.inv_V, mu_h2, [&](size_t Q) { return sv(Q) / (double)aP[Q]; });
-        const double sP = sv(P);
-        s[o + P] = (T)sP;
-        tt[o + P] = (T)at;
-        v[0] += at * sP;
-        v[1] += at * at;
+        const size_t o = m * N + P;
+        const double sv = (double)r[o] - alpha * (double)vv[o];
+        s[o] = (T)sv;
+        z[o] = (T)(sv * ia);
     }
     END_CELLS
-    block_partials<2, 0u>(v, part_ts);
 }
 
+// omega = (t, s) / (t, t); x += alpha y + omega z; r = s - omega t.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_bicg_update(Phys ph, DevState* st, int i, T* __restrict__ x,
-                                                        const T* __restrict__ p, const T* __restrict__ s,
-                                                        const T* __restrict__ tt, T* __restrict__ r,
-                                                        const T* __restrict__ rh, const T* __restrict__ aP,
+                                                        const T* __restrict__ y, const T* __restrict__ z,
+                                                        const T* __restrict__ s, const T* __restrict__ tt,
+                                                        T* __restrict__ r, const T* __restrict__ rh,
                                                         const double* part_ts, double* part_res) {
     MEMBER(ph)
     BicgState& g = (st + mem_)->bicg;
@@ -1936,13 +1952,11 @@ __global__ void __launch_bounds__(kBlock) k_bicg_update(Phys ph, DevState* st, i
     }
     double v[2] = {0.0, 0.0};
     FOR_CELLS(ph)
-    const double ia = 1.0 / (double)aP[P];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         const size_t o = m * N + P;
-        const double sP = (double)s[o];
-        x[o] = (T)((double)x[o] + alpha * ((double)p[o] * ia) + omega * (sP * ia));
-        const double rn = sP - omega * (double)tt[o];
+        x[o] = (T)((double)x[o] + alpha * (double)y[o] + omega * (double)z[o]);
+        const double rn = (double)s[o] - omega * (double)tt[o];
         r[o] = (T)rn;
         v[0] += (double)rh[o] * rn;
         v[1] += rn * rn;
@@ -3653,17 +3667,14 @@ void Ops<T>::bicg_init(const Launch& L, hipStream_t s, const Phys& ph, DevState*
 }
 template <typename T>
 void Ops<T>::bicg_iter(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int i,
-                       double tol2, int maxit, T* x, T* r, const T* rh, T* const p[2], T* const v[2],
-                       T* sv, T* tv, const T* F, const T* aP, double* part_res, double* part_v,
-                       double* part_ts) {
-    T* pold = p[(i + 1) & 1];
-    T* vold = v[(i + 1) & 1];
-    T* pnew = p[i & 1];
-    T* vnew = v[i & 1];
-    LAUNCH(k_bicg_dir<T>, L, s, ph, st, i, tol2, maxit, r, rh, pold, vold, pnew, vnew, F, aP, part_res,
-           part_v);
-    LAUNCH(k_bicg_stab<T>, L, s, ph, st, i, r, vnew, sv, tv, F, aP, part_v, part_ts);
-    LAUNCH(k_bicg_update<T>, L, s, ph, st, i, x, pnew, sv, tv, r, rh, aP, part_ts, part_res);
+                       double tol2, int maxit, T* x, T* r, const T* rh, T* const w[6], const T* F,
+                       const T* aP, double* part_res, double* part_v, double* part_ts) {
+    T *p = w[0], *v = w[1], *y = w[2], *sv = w[3], *z = w[4], *tv = w[5];
+    LAUNCH(k_bicg_dir<T>, L, s, ph, st, i, tol2, maxit, r, p, v, y, aP, part_res);
+    LAUNCH(k_bicg_apply<T>, L, s, ph, st, i, 0, y, v, F, aP, rh, part_v);
+    LAUNCH(k_bicg_half<T>, L, s, ph, st, i, r, v, sv, z, aP, part_v);
+    LAUNCH(k_bicg_apply<T>, L, s, ph, st, i, 1, z, tv, F, aP, sv, part_ts);
+    LAUNCH(k_bicg_update<T>, L, s, ph, st, i, x, y, z, sv, tv, r, rh, part_ts, part_res);
 }
 template <typename T>
 void Ops<T>::energy_setup(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,

@@ -162,9 +162,8 @@ struct Ops {
                           const T* F, const T* aP, const T* src, const T* pn, T* r, T* rh,
                           double* part);
     static void bicg_iter(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int i,
-                          double tol2, int maxit, T* x, T* r, const T* rh, T* const p[2],
-                          T* const v[2], T* sv, T* tv, const T* F, const T* aP, double* part_res,
-                          double* part_v, double* part_ts);
+                          double tol2, int maxit, T* x, T* r, const T* rh, T* const w[6], const T* F,
+                          const T* aP, double* part_res, double* part_v, double* part_ts);
     // Fourier closure: the energy predictor's coefficients and one Jacobi sweep
     static void energy_setup(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                              const T* rn, const T* rs, const T* phi, const T* divu, const T* pn,

@@ -75,7 +75,7 @@ struct Layout {
     size_t xprev;  // previous-step guess: each corrector's last solution
     size_t t0, t1, tw, eaT, esT;  // Fourier closure: T (two rotating), sweep scratch, a_T, s_T
     size_t rm1, um1, rjm1;        // BDF2: rho, u, rho_j at t^{n-1}
-    size_t bicg;                  // momentum BiCGStab: r, rh, p x2, v x2, s, t (3 N each)
+    size_t bicg;                  // momentum BiCGStab: r, rh, p, v, y, s, z, t (3 N each)
     size_t total;
     unsigned max_blocks;     // column length of the partials (all members)
 };
@@ -666,10 +666,8 @@ pisoc_status enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
         const size_t n3 = 3 * ctx->NT();
         T* r = w;
         T* rh = w + n3;
-        T* const pp[2] = {w + 2 * n3, w + 3 * n3};
-        T* const vv[2] = {w + 4 * n3, w + 5 * n3};
-        T* sv = w + 6 * n3;
-        T* tv = w + 7 * n3;
+        // p, v, y = K^-1 p, s, z = K^-1 s, t
+        T* const wk[6] = {w + 2 * n3, w + 3 * n3, w + 4 * n3, w + 5 * n3, w + 6 * n3, w + 7 * n3};
         if (hipMemcpyAsync(x, S.un, n3 * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess) {
             ctx->err = "hipMemcpyAsync failed";
             return PISOC_ERR_HIP;
@@ -679,8 +677,8 @@ pisoc_status enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
         const double tol2 = p.mom_tol * p.mom_tol;
         for (int i = 1;; i += 8) {
             for (int k = i; k < i + 8; ++k)
-                O::bicg_iter(L, s, ph, st, k, tol2, p.mom_maxit, x, r, rh, pp, vv, sv, tv, S.mflux,
-                             S.aP, pres, ctx->part(PS_CG + kBicgV), ctx->part(PS_CG + kBicgTs));
+                O::bicg_iter(L, s, ph, st, k, tol2, p.mom_maxit, x, r, rh, wk, S.mflux, S.aP, pres,
+                             ctx->part(PS_CG + kBicgV), ctx->part(PS_CG + kBicgTs));
             pisoc_status ss = sync_state(ctx);
             if (ss != PISOC_OK) return ss;
             bool all = true;
