@@ -3447,7 +3447,7 @@ Launch make_spmv_launch(int n, int batch, int elem_bytes, int cz_tile) {
         L.v = kRowCells;
         return L;
     }
-    constexpr int TY = kTY * kSpmvRows;
+    const int TY = kTY * spmv_rows(elem_bytes);
     const bool wide = n >= 64 && n % kTX == 0 && n % TY == 0;
     if (!wide && n % kSmallTX != 0) return L;   // nblocks = 0: not available
     const int tx = wide ? kTX : kSmallTX, ty = wide ? TY : kSmallTX;
@@ -3639,7 +3639,7 @@ static void spmv_launch(const Launch& L, const Launch& TL, hipStream_t s, const 
         if (TL.block.x == kSmallTX)
             LAUNCH((k_pcg_spmv_tiled<T, 1, XM, kSmallTX, kSmallTX>), TL, s, pt, SPMV_ARGS);
         else
-            LAUNCH((k_pcg_spmv_tiled<T, kSpmvRows, XM, kTX, kTY>), TL, s, pt, SPMV_ARGS);
+            LAUNCH((k_pcg_spmv_tiled<T, spmv_rows(sizeof(T)), XM, kTX, kTY>), TL, s, pt, SPMV_ARGS);
     } else {
         LAUNCH((k_pcg_spmv<T, XM>), L, s, ph, SPMV_ARGS);
     }

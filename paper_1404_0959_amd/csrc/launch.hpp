@@ -41,13 +41,14 @@ Launch make_tiled_launch(int n, int batch = 1, int cz_tile = 0);
 // n = 64 kRowCells and FP32: the full-row form, blocks of kRowWaves
 // wavefronts each owning one x-row (kRowCells cells per lane), about
 // kRowBlocks blocks per member (v = kRowCells; in FP64 its registers would
-// not fit).  Otherwise, for n a multiple of 64, tiles of 64 x (8 kSpmvRows)
-// cells, 64 x 8 threads each owning kSpmvRows rows (v = 0); for the other
-// multiples of kSmallTX, tiles of kSmallTX x kSmallTX cells, one thread per
+// not fit).  Otherwise, for n a multiple of 64 (and of 8 spmv_rows), tiles of
+// 64 x (8 spmv_rows) cells, 64 x 8 threads each owning spmv_rows rows (v = 0;
+// two rows in FP64 halve the tile's y halo; in FP32 two measured no faster);
+// for the other multiples of kSmallTX, tiles of kSmallTX x kSmallTX cells, one thread per
 // column (block.x = kSmallTX); nblocks is 0 when none is available.  Tiles
 // march over at least 8 planes, or exactly min(cz_tile, n) when cz_tile > 0
 // (a tuned choice; the full-row form ignores it).
-constexpr int kSpmvRows = 1;
+constexpr int spmv_rows(int elem_bytes) { return elem_bytes == 8 ? 2 : 1; }
 constexpr int kSmallTX = 16;
 constexpr int kRowCells = 4, kRowWaves = 8, kRowBlocks = 256;
 Launch make_spmv_launch(int n, int batch, int elem_bytes, int cz_tile = 0);

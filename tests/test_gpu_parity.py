@@ -109,7 +109,7 @@ def test_helm_apply_parity(P, ora, n):
 
 @pytest.mark.parametrize("n", [16, 40, 128, 256])
 def test_helm_solve_parity(P, ora, n):
-    """128 and 256 run the 64 x 8 tiled CG kernel (FP64)."""
+    """128 and 256 run the 64 x 16 tiled CG kernel (FP64, two rows per thread)."""
     import torch
     rng = np.random.default_rng(100 + n)
     h = 2 * math.pi / n
