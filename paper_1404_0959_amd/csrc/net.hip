@@ -1,8 +1,10 @@
 // net.hip -- the learned pressure-guess network on gfx950: four periodic
 // 3x3x3 convolutions (2 -> 16 -> 16 -> 16 -> 1, ReLU after the first three, no
 // biases) evaluated with BF16 operands and FP32 accumulation on the matrix
-// cores (v_mfma_f32_16x16x16_bf16), plus the training kernels (data and weight
-// gradients, MSE loss, Adam) and the C ABI of the network.
+// cores (v_mfma_f32_16x16x32_bf16 in the forward 16 -> 16 layers,
+// v_mfma_f32_16x16x16_bf16 elsewhere), plus the training kernels (data and
+// weight gradients, MSE and residual losses, Adam) and the C ABI of the
+// network.
 //
 // GEMM view of one layer: for 16 consecutive cells along x (one wavefront),
 // D[cell][co] = sum over K of A[cell][k] B[k][co] with k = (tap, ci).  With 16
