@@ -434,7 +434,8 @@ def main():
                                f"{args.p_tol:g}, seed {args.seed}",
                    "grid": args.n, "mode": head,
                    "guess": (f"learned, audited (trial of the rejected choice after {args.guess_audit} "
-                             f"steps, the interval doubling up to {16 * args.guess_audit})"
+                             f"steps, the interval doubling up to {16 * args.guess_audit}; no trial "
+                             f"of a guess that costs the whole zero-start solve or more)"
                              if head == "fp32_learned" else "zero")},
         "roofline": roof,
         "cpu_baseline": cpu,

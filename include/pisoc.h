@@ -133,7 +133,9 @@ typedef struct {
                                   once after k steps and then at intervals that double, up
                                   to 16 k, while each trial confirms the verdict (back to k
                                   when one overturns it; PISOC_FLAG_GUESS_SKIPPED marks steps
-                                  that went without it).  Eager ensemble steps audit the
+                                  that went without it).  A rejected guess whose cost is at
+                                  least the mean iterations of the zero-start solve is not
+                                  tried: saving every iteration would not pay for it.  Eager ensemble steps audit the
                                   same way; a captured ensemble step keeps the verdict
                                   its graph was built with (without the periodic trial) */
     int32_t two_way;           /* != 0: two-way coupling.  The momentum equation is the

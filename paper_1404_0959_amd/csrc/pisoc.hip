@@ -969,7 +969,8 @@ bool guess_available(const pisoc_ctx* ctx) {
 // The guess is used for a solve when the iterations it saves exceed its cost
 // (both as running means); until both options have been measured each is
 // tried once, and every guess_audit-th step takes the other option once so
-// that the mean of the unused one stays current.
+// that the mean of the unused one stays current (not a rejected guess whose
+// cost is at least the zero-start solve's iterations: no saving could pay it).
 constexpr int kMaxProbeFactor = 16;
 bool audit_measured(const pisoc_ctx* ctx);
 
@@ -989,7 +990,10 @@ void audit_decide(pisoc_ctx* ctx) {
         else {
             const bool pays = audit_pays(ctx, c);
             A.verdict[c] = pays;
-            use = A.probing ? !pays : pays;
+            // a rejected guess whose cost reaches the whole zero-start solve
+            // could not pay even by saving every iteration: no trial of it
+            const bool hopeless = !pays && A.cost >= A.it_zero[c];
+            use = A.probing && !hopeless ? !pays : pays;
         }
         A.use[c] = use;
     }
