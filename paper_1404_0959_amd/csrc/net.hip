@@ -39,6 +39,16 @@ __device__ inline float bf2f(uint16_t b) {
 
 __device__ inline int wrapn(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
+// FP32 -> BF16, round to nearest even, with gfx950's conversion instruction
+// (v_cvt_pk_bf16_f32): the same rounding as f2bf for finite values, without
+// its branch for NaN.
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t bf16x2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v2f{a, b}, v2bf));
+}
+__device__ inline uint16_t bf16x1(float a) { return __builtin_bit_cast(uint16_t, (__bf16)a); }
+
 template <int CINP> constexpr int nkb() { return CINP == 16 ? 27 : 7; }
 
 // (tap, channel) of entry kk (0..15) of K-block kb.
@@ -110,16 +120,16 @@ __global__ void __launch_bounds__(256) k_conv(int n, int batch, const uint16_t* 
             } else if (relu) {
                 v = v > 0.f ? v : 0.f;
             }
-            out[P * 16 + nn] = f2bf(v);
+            out[P * 16 + nn] = bf16x1(v);
         }
     }
 }
 
-// Forward pass of a 16-input-channel layer with input reuse across output
-// rows.  A wavefront owns 16 cells along x of a block of kRY x kRZ output rows
-// (y, z) and walks the (kRY + 2) x (kRZ + 2) input rows that block touches,
-// each loaded once and fed to the matrix cores for every output row and tap
-// it contributes to.
+// Tiles of the first and last layers: a wavefront owns 16 cells along x of a
+// block of kRY x kRZ output rows (y, z) and walks the (kRY + 2) x (kRZ + 2)
+// input rows that block touches, each loaded once and fed to the matrix cores
+// for every output row and tap it contributes to (the 16 -> 16 layers march
+// along z with kRY rows per wavefront).
 constexpr int kRY = 4, kRZ = 4;
 // input rows whose loads are in flight ahead of the products that use them
 // (for the first and last layers; 8 measured fastest of 2, 4, 6, 8)
@@ -132,9 +142,9 @@ constexpr int kAhead = 8;
 // 2p + 1 in groups 2-3, 8 channels (16 bytes) of one cell per lane.  Output row
 // oy reads items 3 oy .. 3 oy + 8, the 5 pairs from floor(3 oy / 2) on, whose
 // weight operand depends only on the parity c of oy, the pair's slot s in that
-// run and dz: 30 operands, held in registers.  240 products per tile of
-// 16 x kRY x kRZ cells (432 with K = 16), 10 % of their entries the zero
-// halves at the ends of odd and even runs.
+// run and dz: 30 operands, held in registers.  60 products per output plane of
+// 16 x kRY cells (108 with K = 16), 10 % of their entries the zero halves at
+// the ends of odd and even runs.
 constexpr int kItems = 3 * (kRY + 2), kPairs = kItems / 2, kSlots = 5;
 static_assert(kItems % 2 == 0, "items pair up within a plane");
 
@@ -148,13 +158,16 @@ __device__ inline void store_rows(const v4f (&acc)[kRY][kRZ], uint16_t* __restri
 #pragma unroll
         for (int oy = 0; oy < kRY; ++oy) {
             const size_t cell = (size_t)x + (size_t)n * ((size_t)(j0 + oy) + (size_t)n * (k0 + oz));
-            v4s q;
+            float v[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float v = acc[oy][oz][e];
-                q[e] = (short)f2bf(relu && !(v > 0.f) ? 0.f : v);
+                const float a = acc[oy][oz][e];
+                v[e] = relu && !(a > 0.f) ? 0.f : a;
             }
-            *reinterpret_cast<v4s*>(out + cell * 16 + 4 * g) = q;
+            uint2 q;
+            q.x = bf16x2(v[0], v[1]);
+            q.y = bf16x2(v[2], v[3]);
+            *reinterpret_cast<uint2*>(out + cell * 16 + 4 * g) = q;
         }
 }
 
@@ -163,22 +176,56 @@ __device__ inline v4f mfma_k32(v8s a, v8s b, v4f c) {
                                                    __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
 }
 
-__global__ void __launch_bounds__(256) k_conv16_pairs(int n, int batch,
+// The 16 -> 16 layer as a z-march.  A wavefront owns 16 cells along x times
+// kRY rows along y and walks a chunk of ZC output planes: input plane by input
+// plane (ZC + 2 of them, each loaded once, 9 pair items of 16 bytes per
+// lane), it issues the products of the three output planes the input plane
+// reaches (dz = -1, 0, 1) into a ring of three planes of accumulators, and
+// stores an output plane once its last input plane (dz = +1) is done.  The
+// weight operands are loaded once per wavefront; each item of the next input
+// plane is loaded into its register right after the item's last product, so
+// a whole plane of products covers the load.  The plane loop is unrolled in
+// full (ZC a template parameter), so that every ring slot and edge test is a
+// constant and the loads stay in flight across planes (with run-time tests the
+// compiler drained them at every branch: 1.65 against 1.12 ms for the
+// network at 256^3).  Against one wavefront per 16 x kRY x kRZ tile, which
+// reread 6 input planes per 4 output planes and reloaded the weights per
+// tile, the layer takes about 290 instead of 480 us at 256^3.
+__device__ inline void store_plane_rows(const v4f (&acc)[kRY], uint16_t* __restrict__ out, int n,
+                                        int x, int j0, int kz, int g, int relu) {
+#pragma unroll
+    for (int oy = 0; oy < kRY; ++oy) {
+        const size_t cell = (size_t)x + (size_t)n * ((size_t)(j0 + oy) + (size_t)n * kz);
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float a = acc[oy][e];
+            v[e] = relu && !(a > 0.f) ? 0.f : a;
+        }
+        uint2 q;
+        q.x = bf16x2(v[0], v[1]);
+        q.y = bf16x2(v[2], v[3]);
+        *reinterpret_cast<uint2*>(out + cell * 16 + 4 * g) = q;
+    }
+}
+
+template <int ZC>
+__global__ void __launch_bounds__(256, 2) k_conv16_zm(int n, int batch,
                                                       const uint16_t* __restrict__ in,
                                                       const v8s* __restrict__ wpp, int relu,
                                                       uint16_t* __restrict__ out) {
     const int lane = threadIdx.x & 63;
     const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int segs = n / 16, nyb = n / kRY, nzb = n / kRZ;
-    const long nwaves = (long)batch * nzb * nyb * segs;
+    const int segs = n / 16, nyb = n / kRY, nzc = n / ZC;
+    const long nwaves = (long)batch * nzc * nyb * segs;
     if (wave >= nwaves) return;  // whole wavefront; no block barrier below
     const int iseg = (int)(wave % segs);
     long rest = wave / segs;
     const int j0 = (int)(rest % nyb) * kRY;
     rest /= nyb;
-    const int k0 = (int)(rest % nzb) * kRZ;
-    const int b = (int)(rest / nzb);
-    const size_t N = (size_t)n * n * n;
+    const int k0 = (int)(rest % nzc) * ZC;
+    const int b = (int)(rest / nzc);
+    const size_t N = (size_t)n * n * n, nn = (size_t)n * n;
     const int m = lane & 15, g = lane >> 4, h = g >> 1;
     v8s B[2][kSlots][3];
 #pragma unroll
@@ -187,55 +234,54 @@ __global__ void __launch_bounds__(256) k_conv16_pairs(int n, int batch,
         for (int s = 0; s < kSlots; ++s)
 #pragma unroll
             for (int dz = 0; dz < 3; ++dz) B[c][s][dz] = wpp[((c * kSlots + s) * 3 + dz) * 64 + lane];
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int s = 0; s < kSlots; ++s)
-#pragma unroll
-            for (int dz = 0; dz < 3; ++dz) asm volatile("" : "+v"(B[c][s][dz]));
-    v4f acc[kRY][kRZ];
-#pragma unroll
-    for (int oy = 0; oy < kRY; ++oy)
-#pragma unroll
-        for (int oz = 0; oz < kRZ; ++oz) acc[oy][oz] = v4f{0.f, 0.f, 0.f, 0.f};
-    // this lane's cell of each pair within a plane (item 2p + h)
+    // this lane's element offset of each pair item within a plane
     int off[kPairs];
 #pragma unroll
     for (int p = 0; p < kPairs; ++p) {
         const int r = 2 * p + h, iy = r / 3, q = r % 3;
-        off[p] = n * wrapn(j0 - 1 + iy, n) + wrapn(iseg * 16 + m + q - 1, n);
+        off[p] = (n * wrapn(j0 - 1 + iy, n) + wrapn(iseg * 16 + m + q - 1, n)) * 16 + 8 * (g & 1);
     }
-    const uint16_t* inb = in + (size_t)b * N * 16 + 8 * (g & 1);
-    // 4 pairs in flight keeps the kernel at 2 waves per SIMD (measured faster
-    // than 6 or 9 at 1 wave)
-    constexpr int kLoads = (kRZ + 2) * kPairs, kAh = 4;
-    auto load = [&](int t, v8s& a) {
-        const size_t plane = (size_t)n * n * wrapn(k0 - 1 + t / kPairs, n);
-        a = *reinterpret_cast<const v8s*>(inb + (plane + off[t % kPairs]) * 16);
-    };
-    v8s abuf[kAh + 1];
-#pragma clang loop unroll(full)
-    for (int t = 0; t < kAh; ++t) load(t, abuf[t]);
-#pragma clang loop unroll(full)
-    for (int t = 0; t < kLoads; ++t) {
-        const int iz = t / kPairs, p = t % kPairs;
-        if (t + kAh < kLoads) load(t + kAh, abuf[(t + kAh) % (kAh + 1)]);
-        __builtin_amdgcn_sched_barrier(0);
-        const v8s a = abuf[t % (kAh + 1)];
-#pragma clang loop unroll(full)
-        for (int oz = 0; oz < kRZ; ++oz) {
-            const int dz = iz - 1 - oz;
-            if (dz < -1 || dz > 1) continue;
-#pragma clang loop unroll(full)
-            for (int oy = 0; oy < kRY; ++oy) {
-                const int s = p - (3 * oy) / 2;
-                if (s < 0 || s >= kSlots) continue;
-                acc[oy][oz] = mfma_k32(B[oy & 1][s][dz + 1], a, acc[oy][oz]);
+    const uint16_t* inb = in + (size_t)b * N * 16;
+    uint16_t* outb = out + (size_t)b * N * 16;
+    auto plane_ptr = [&](int t) { return inb + nn * 16 * (size_t)wrapn(k0 - 1 + t, n); };
+    v8s a[kPairs];
+    {
+        const uint16_t* pb = plane_ptr(0);
+#pragma unroll
+        for (int p = 0; p < kPairs; ++p) a[p] = *reinterpret_cast<const v8s*>(pb + off[p]);
+    }
+    v4f acc[3][kRY];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int oy = 0; oy < kRY; ++oy) acc[r][oy] = v4f{0.f, 0.f, 0.f, 0.f};
+    // fully unrolled: every plane's output rows and ring slots are constants
+#pragma unroll
+    for (int t = 0; t < ZC + 2; ++t) {
+        const bool more = t + 1 < ZC + 2;
+        const uint16_t* pn = plane_ptr(more ? t + 1 : t);
+#pragma unroll
+        for (int p = 0; p < kPairs; ++p) {
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int oz = t - 1 - dz;   // output plane, ring slot oz mod 3
+                if (oz < 0 || oz >= ZC) continue;
+#pragma unroll
+                for (int oy = 0; oy < kRY; ++oy) {
+                    const int s = p - (3 * oy) / 2;
+                    if (s < 0 || s >= kSlots) continue;
+                    acc[oz % 3][oy] = mfma_k32(B[oy & 1][s][dz + 1], a[p], acc[oz % 3][oy]);
+                }
             }
+            if (more) a[p] = *reinterpret_cast<const v8s*>(pn + off[p]);
         }
-        __builtin_amdgcn_sched_barrier(0);
+        // output plane t - 2 has had its last input plane (dz = +1)
+        if (t >= 2) {
+            store_plane_rows(acc[(t - 2) % 3], outb, n, iseg * 16 + m, j0, k0 + t - 2, g, relu);
+#pragma unroll
+            for (int oy = 0; oy < kRY; ++oy) acc[(t - 2) % 3][oy] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
     }
-    store_rows(acc, out + (size_t)b * N * 16, n, iseg * 16 + m, j0, k0, g, relu);
 }
 
 // Last layer (16 inputs, 1 output): the kRY x kRZ = 16 output rows of the block
@@ -492,7 +538,7 @@ __global__ void k_pack_final(const float* __restrict__ w, v4s* __restrict__ wfin
     wfin[t] = v;
 }
 
-// Pack a 16 -> 16 layer for k_conv16_pairs: operand (c, s, dz) at lane
+// Pack a 16 -> 16 layer for k_conv16_zm: operand (c, s, dz) at lane
 // (n = co, g) holds in entry j the weight of channel 8 (g & 1) + j for item
 // rr = 2 s + (g >> 1) - c of the output row's run, rr = 3 (dy + 1) + dx + 1,
 // zero outside 0..8.
@@ -686,7 +732,7 @@ size_t net_weight_offset(int layer) {
 // Forward operands: layer 1 for k_conv (7 K-blocks), layers 2-4 (27 each),
 // layer 1 again for k_conv4_rows (9 K-blocks), layer 4 for
 // k_conv16_final_rows (27 taps x 4 channel groups), then layers 2 and 3 for
-// k_conv16_pairs (30 K = 32 operands each).
+// k_conv16_zm (30 K = 32 operands each).
 constexpr size_t kPackV4 = (size_t)(7 + 27 + 27 + 27 + 9) * 64 + 27 * 4;
 constexpr int kPairOps = 2 * kSlots * 3 * 64;
 static_assert(kPackV4 * sizeof(v4s) % sizeof(v8s) == 0, "pair operands stay 16-byte aligned");
@@ -726,13 +772,36 @@ static dim3 conv_rows_grid(int n, int batch) {
     return dim3((unsigned)((waves + 3) / 4));
 }
 
+// Output planes per wavefront of k_conv16_zm: the longest chunk (16, 8 or 4
+// planes, dividing n) that still gives at least 4096 wavefronts (32 planes
+// would spill registers).
+static int zm_chunk(int n, int batch) {
+    const long per_plane = (long)batch * (n / kRY) * (n / 16);
+    for (int zc = 16; zc > 4; zc /= 2)
+        if (n % zc == 0 && per_plane * (n / zc) >= 4096) return zc;
+    return 4;
+}
+static unsigned zm_blocks(int n, int batch, int zc) {
+    const long waves = (long)batch * (n / zc) * (n / kRY) * (n / 16);
+    return (unsigned)((waves + 3) / 4);
+}
+
 void net_forward(hipStream_t s, int n, int batch, const void* wpk, const uint16_t* x4,
                  uint16_t* a, uint16_t* b, float* y, float yscale) {
     const v4s* p = reinterpret_cast<const v4s*>(wpk);
     const dim3 GR = conv_rows_grid(n, batch), B(256);
     hipLaunchKernelGGL(k_conv4_rows, GR, B, 0, s, n, batch, x4, p + (7 + 27 + 27 + 27) * 64, a);
-    hipLaunchKernelGGL(k_conv16_pairs, GR, B, 0, s, n, batch, a, pair_ops(wpk, 1), 1, b);
-    hipLaunchKernelGGL(k_conv16_pairs, GR, B, 0, s, n, batch, b, pair_ops(wpk, 2), 1, a);
+    const int zc = zm_chunk(n, batch);
+    const dim3 GZ(zm_blocks(n, batch, zc));
+    auto layer = [&](const uint16_t* src, const v8s* w, uint16_t* dst) {
+        switch (zc) {
+        case 16: hipLaunchKernelGGL(k_conv16_zm<16>, GZ, B, 0, s, n, batch, src, w, 1, dst); break;
+        case 8: hipLaunchKernelGGL(k_conv16_zm<8>, GZ, B, 0, s, n, batch, src, w, 1, dst); break;
+        default: hipLaunchKernelGGL(k_conv16_zm<4>, GZ, B, 0, s, n, batch, src, w, 1, dst); break;
+        }
+    };
+    layer(a, pair_ops(wpk, 1), b);
+    layer(b, pair_ops(wpk, 2), a);
     hipLaunchKernelGGL(k_conv16_final_rows, GR, B, 0, s, n, batch, a,
                        reinterpret_cast<const v4s*>(wpk) + (7 + 27 + 27 + 27 + 9) * 64, y, yscale);
 }
