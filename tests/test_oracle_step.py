@@ -409,3 +409,27 @@ def test_stats_with_variable_density(ora):
     assert abs(s["ke"] - 3 / 16) < 1e-14
     assert abs(s["rho_rms"] - math.sqrt(1 / 8)) < 1e-14
     assert abs(s["mach_rms"] - math.sqrt(0.5) / math.sqrt(GAMMA * 5.0)) < 1e-14
+
+
+def test_initial_flux_is_the_product_form(ora):
+    """The mass flux on a face is I4(rho) I4(u) A (the reading of the face
+    flux: the product of the interpolated density and velocity), not I4(rho u).
+    With rho = 1 + e cos(kx) and u = U cos(kx) along x, and T(t) = (9 cos(t/2)
+    - cos(3t/2))/8 the I4 symbol (t = kh), the face x_f = x + h/2 carries
+    A U T cos(k x_f) (1 + e T cos(k x_f)); I4(rho u) would give
+    A U [T cos(k x_f) + e (1 + T(2t) cos(2 k x_f)) / 2], which differs by
+    order e at this kh."""
+    n, k, e, U = 16, 3, 0.3, 0.7
+    h, (x, y, z) = grid(n)
+    rho = 1.0 + e * np.cos(k * x)
+    u = np.stack([U * np.cos(k * x), np.zeros_like(x), np.zeros_like(x)])
+    o = ora.Oracle(n, rho, u, gamma=GAMMA, C_=10.0, mu=1e-3)
+    phi = o.get(ora.PHI)
+    T = lambda t: (9 * math.cos(t / 2) - math.cos(3 * t / 2)) / 8
+    t = k * h
+    cf = np.cos(k * (x + h / 2))
+    want = h * h * U * T(t) * cf * (1 + e * T(t) * cf)
+    other = h * h * U * (T(t) * cf + e * (1 + T(2 * t) * np.cos(2 * k * (x + h / 2))) / 2)
+    assert np.max(np.abs(phi[0] - want)) <= 1e-14 * np.max(np.abs(want))
+    assert np.max(np.abs(phi[1])) == 0.0 and np.max(np.abs(phi[2])) == 0.0
+    assert np.max(np.abs(other - want)) > 1e-2 * np.max(np.abs(want))
