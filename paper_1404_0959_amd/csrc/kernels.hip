@@ -1360,16 +1360,21 @@ __global__ void __launch_bounds__(TX * NTY) k_pcg_spmv_tiled(
     block_partials<CG_COLS, 0u>(acc, part_out);
 }
 
-// Row form for n = 64 V: a block of kRowWaves wavefronts owns as many
-// consecutive full x-rows (wavefront v: row j0 + v; lane l: cells
+// Row form for n = 64 V H: a block of kRowWaves wavefronts owns kRowWaves / H
+// consecutive full x-rows, H wavefronts per row (wavefront v: row j0 + v / H,
+// lanes 64 (v % H) .. 64 (v % H) + 63 of the row; lane l of the row: cells
 // x = V l .. V l + V - 1, one vector load per field) and marches along z over
-// cz planes.  A whole periodic row lives in one wavefront, so the x
-// neighbours come from the lane's own cells and one lane rotation and no x
-// halo is read.  y neighbours come from LDS rows (halo 2 for w, 1 for p)
-// loaded by wavefronts 0-5; z neighbours from per-lane register queues, the
-// lower z face coefficient carried over from the plane below.  Prefetches
-// past the chunk's last needed plane are clamped to planes already read.
-template <typename T, int V, int XM>
+// cz planes.  A whole periodic row lives in the block, so no x halo is read:
+// with H = 1 the x neighbours come from the lane's own cells and one lane
+// rotation, with H = 2 (FP64: 2 cells per lane, whose registers fit where 4
+// would not) from the row's LDS copy that the y neighbours use anyway.  y
+// neighbours come from LDS rows (halo 2 for w, 1 for p): with H = 1 loaded by
+// wavefronts 0-5 (one halo row each), with H = 2 the p halo by wavefronts 0-3
+// (one half row each) and the w halo by 4-7 (both halves of one row each).  z
+// neighbours come from per-lane register queues, the lower z face coefficient
+// carried over from the plane below.  Prefetches past the chunk's last needed
+// plane are clamped to planes already read.
+template <typename T, int V, int H, int XM>
 __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     Phys ph, DevState* st, int k, const T* __restrict__ rin, T* __restrict__ rout,
     const T* __restrict__ diag, const T* __restrict__ w, const T* __restrict__ pold,
@@ -1378,7 +1383,8 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     int fresh, int maxit, int xzero) {
     constexpr bool UPD = XM > 0, XE = XM == 2;
     using VT = T __attribute__((ext_vector_type(V)));
-    static_assert(kRowWaves >= 6, "wavefronts 0-5 load the y halo rows");
+    static_assert(H == 1 ? kRowWaves >= 6 : H == 2 && kRowWaves == 8,
+                  "y halo loads: wavefronts 0-5 (one per row) or 0-7 (two per row)");
     MEMBER(ph)
     if (k > (st + mem_)->pcg.it_stop) return;   // see k_pcg_spmv
     const CgHead h = cg_head(ph, (st + mem_)->pcg, MEMBER_FIRST(), mem_, k, part_in, nb_in, fresh,
@@ -1386,21 +1392,22 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     const T alpha = (T)h.alpha, beta = (T)h.beta;
     const T inv_h2 = (T)ph.inv_h2;
     const int n = ph.n, cz = ph.cz;   // n == 64 V
-    constexpr int TY = kRowWaves;
+    constexpr int TY = kRowWaves / H, RW = 64 * H;   // rows per block, lanes per row
     const int lane = threadIdx.x, wv = threadIdx.y;
+    const int r = wv / H, gl = (wv % H) * 64 + lane;   // row in the block, lane in the row
     const int j0 = bp_.y * TY;
     const int k0 = bz_ * cz;
     const int k1 = k0 + cz < n ? k0 + cz : n;
     const size_t nn = (size_t)n * n;
-    __shared__ VT wl[TY + 4][64];   // w of rows j0 - 2 .. j0 + TY + 1
-    __shared__ VT pl[TY + 2][64];   // p of rows j0 - 1 .. j0 + TY
+    __shared__ VT wl[TY + 4][RW];   // w of rows j0 - 2 .. j0 + TY + 1
+    __shared__ VT pl[TY + 2][RW];   // p of rows j0 - 1 .. j0 + TY
     auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
     auto ld = [](const T* f, size_t o) { return *reinterpret_cast<const VT*>(f + o); };
     // outputs and x stream past the caches (stream_st), keeping L2 for the
     // halo rows and planes still to be read
     auto st_v = [](T* f, size_t o, VT v) { stream_st(reinterpret_cast<VT*>(f + o), v); };
     auto ld_x = [](const T* f, size_t o) { return stream_ld(reinterpret_cast<const VT*>(f + o)); };
-    const size_t col = base_ + (size_t)n * (j0 + wv) + (size_t)V * lane;
+    const size_t col = base_ + (size_t)n * (j0 + r) + (size_t)V * gl;
     const CgX<T> xu = cg_x<T, XM>((st + mem_)->pcg, k, h.alpha, xzero);
     if (h.stop) {
         if ((UPD || xzero) && !h.skip) {
@@ -1417,14 +1424,26 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     auto resf = [&](VT ro, VT qo) -> VT { return UPD ? ro - alpha * qo : ro; };
     auto dirf = [&](VT z, VT po) -> VT { return UPD ? z + beta * po : z; };
     auto ldu = [&](const T* f, size_t o) { return UPD ? ld(f, o) : VT(T(0)); };
-    // this wavefront's y halo row: w rows j0-2, j0-1, j0+TY, j0+TY+1 (waves
-    // 0-3), p rows j0-1, j0+TY (waves 4-5, from r, q, diag and p_old); waves
-    // 6.. read their own w row so that every load is unconditional.  Waves
-    // other than 4-5 point all four halo loads at the same w row (cache hits).
-    const int hrow = wv < 2 ? j0 - 2 + wv : wv < 4 ? j0 + TY - 2 + wv
-                   : wv == 4 ? j0 - 1 : wv == 5 ? j0 + TY : j0 + wv;
-    const size_t hcol = base_ + (size_t)n * wr(hrow) + (size_t)V * lane;
-    const bool phalo = wv == 4 || wv == 5;
+    // this wavefront's y halo loads (h1..h4 from hsrc..hqsrc at hc1..hc4).
+    // H = 1: w rows j0-2, j0-1, j0+TY, j0+TY+1 (waves 0-3), p rows j0-1,
+    // j0+TY (waves 4-5, from r, q, diag and p_old); waves 6.. read their own
+    // w row so that every load is unconditional; waves other than 4-5 point all
+    // four loads at the same w row (cache hits).  H = 2: p halves of rows j0-1
+    // and j0+TY (waves 0-3), both w halves (h1, h2) of rows j0-2, j0-1,
+    // j0+TY, j0+TY+1 (waves 4-7; h3, h4 repeat h1).
+    const bool phalo = H == 1 ? wv == 4 || wv == 5 : wv < 4;
+    int hrow, hhalf = lane;
+    if (H == 1) {
+        hrow = wv < 2 ? j0 - 2 + wv : wv < 4 ? j0 + TY - 2 + wv : wv == 4 ? j0 - 1 : wv == 5 ? j0 + TY : j0 + wv;
+    } else if (phalo) {
+        hrow = wv < 2 ? j0 - 1 : j0 + TY;
+        hhalf = (wv % 2) * 64 + lane;
+    } else {
+        hrow = wv < 6 ? j0 - 6 + wv : j0 + TY - 6 + wv;
+    }
+    const size_t hc1 = base_ + (size_t)n * wr(hrow) + (size_t)V * hhalf;
+    const size_t hc2 = H == 2 && !phalo ? hc1 + (size_t)V * 64 : hc1;
+    const size_t hc3 = hc1, hc4 = hc1;
     const T* hsrc = phalo ? rin : w;
     const T* hdsrc = phalo ? diag : w;
     const T* hosrc = phalo ? pold : w;
@@ -1450,8 +1469,8 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     VT xc = XE ? ld_x(x, Q0) : VT(T(0)), xn1 = xc;
     VT o2c = XE ? ld_x(pold2, Q0) : VT(T(0)), o2n1 = o2c;
     VT rnx = ld(rin, Q1), qnx = ldu(qold, Q1), dnx = ld(diag, Q1), onx = ldu(pold, Q1);
-    VT h1 = ld(hsrc, hcol + plane(k0)), h2 = ld(hdsrc, hcol + plane(k0));
-    VT h3 = ldu(hosrc, hcol + plane(k0)), h4 = ldu(hqsrc, hcol + plane(k0));
+    VT h1 = ld(hsrc, hc1 + plane(k0)), h2 = ld(hdsrc, hc2 + plane(k0));
+    VT h3 = ldu(hosrc, hc3 + plane(k0)), h4 = ldu(hqsrc, hc4 + plane(k0));
     VT kzm = (T(9) * (wm1 + w0) - (wmm + wp1)) * T(0.0625);
     auto from_left = [&](T v) { return __shfl(v, (lane + 63) & 63, 64); };
     auto from_right = [&](T v) { return __shfl(v, (lane + 1) & 63, 64); };
@@ -1462,47 +1481,73 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
         const VT ip = jv(dnx), zp = rp * ip;
         const VT pp = dirf(zp, onx);
         const VT dn = dnx, on = onx;
-        const VT hw = h1;
+        const VT hw = h1, hw2 = h2;
         VT hp = VT(T(0));
         if (phalo) hp = dirf(resf(h1, h4) * jv(h2), h3);
         {
             const int kw = kk + 3 < k1 + 1 ? kk + 3 : k1 + 1;   // last w plane needed: k1 + 1
             const int kp = kk + 2 < k1 ? kk + 2 : k1;           // last p plane needed: k1
             const int kh = kk + 1 < k1 - 1 ? kk + 1 : k1 - 1;   // last halo plane: k1 - 1
-            const size_t Qp = col + plane(kp), Qh = hcol + plane(kh);
+            const size_t Qp = col + plane(kp), Qh = plane(kh);
             wp2n = ld(w, col + plane(kw));
             rnx = ld(rin, Qp);
             qnx = ldu(qold, Qp);
             dnx = ld(diag, Qp);
             onx = ldu(pold, Qp);
-            h1 = ld(hsrc, Qh);
-            h2 = ld(hdsrc, Qh);
-            h3 = ldu(hosrc, Qh);
-            h4 = ldu(hqsrc, Qh);
+            h1 = ld(hsrc, hc1 + Qh);
+            h2 = ld(hdsrc, hc2 + Qh);
+            h3 = ldu(hosrc, hc3 + Qh);
+            h4 = ldu(hqsrc, hc4 + Qh);
             if (XE) {
                 const size_t Qx = col + nn * (size_t)(kk + 1 < k1 ? kk + 1 : kk);
                 xn1 = ld_x(x, Qx);
                 o2n1 = ld_x(pold2, Qx);
             }
         }
-        wl[wv + 2][lane] = w0;
-        pl[wv + 1][lane] = pc;
-        if (wv < 2) wl[wv][lane] = hw;
-        else if (wv < 4) wl[TY + wv][lane] = hw;
-        else if (wv == 4) pl[0][lane] = hp;
-        else if (wv == 5) pl[TY + 1][lane] = hp;
+        wl[r + 2][gl] = w0;
+        pl[r + 1][gl] = pc;
+        if (H == 1) {
+            if (wv < 2) wl[wv][lane] = hw;
+            else if (wv < 4) wl[TY + wv][lane] = hw;
+            else if (wv == 4) pl[0][lane] = hp;
+            else if (wv == 5) pl[TY + 1][lane] = hp;
+        } else if (phalo) {
+            pl[wv < 2 ? 0 : TY + 1][hhalf] = hp;
+        } else {
+            const int slot = wv < 6 ? wv - 4 : TY + wv - 4;
+            wl[slot][lane] = hw;
+            wl[slot][64 + lane] = hw2;
+        }
         lds_barrier();
-        const VT ym2 = wl[wv][lane], ym1 = wl[wv + 1][lane], yp1 = wl[wv + 3][lane], yp2 = wl[wv + 4][lane];
-        const VT pym = pl[wv][lane], pyp = pl[wv + 2][lane];
+        const VT ym2 = wl[r][gl], ym1 = wl[r + 1][gl], yp1 = wl[r + 3][gl], yp2 = wl[r + 4][gl];
+        const VT pym = pl[r][gl], pyp = pl[r + 2][gl];
+        // H = 2: the x neighbours' cells (periodic row of RW lanes)
+        VT wL = VT(T(0)), wR = VT(T(0)), pL = VT(T(0)), pR = VT(T(0));
+        if (H == 2) {
+            const int gm = (gl + RW - 1) % RW, gp = (gl + 1) % RW;
+            wL = wl[r + 2][gm];
+            wR = wl[r + 2][gp];
+            pL = pl[r + 1][gm];
+            pR = pl[r + 1][gp];
+        }
         lds_barrier();
         // w at x - 2 .. x + V + 1 and p at x - 1 .. x + V of this lane's cells
         T wx[V + 4], px[V + 2];
-        wx[0] = from_left(w0[V - 2]);
-        wx[1] = from_left(w0[V - 1]);
-        wx[V + 2] = from_right(w0[0]);
-        wx[V + 3] = from_right(w0[1]);
-        px[0] = from_left(pc[V - 1]);
-        px[V + 1] = from_right(pc[0]);
+        if (H == 1) {
+            wx[0] = from_left(w0[V - 2]);
+            wx[1] = from_left(w0[V - 1]);
+            wx[V + 2] = from_right(w0[0]);
+            wx[V + 3] = from_right(w0[1]);
+            px[0] = from_left(pc[V - 1]);
+            px[V + 1] = from_right(pc[0]);
+        } else {
+            wx[0] = wL[V - 2];
+            wx[1] = wL[V - 1];
+            wx[V + 2] = wR[0];
+            wx[V + 3] = wR[1];
+            px[0] = pL[V - 1];
+            px[V + 1] = pR[0];
+        }
 #pragma unroll
         for (int i = 0; i < V; ++i) {
             wx[i + 2] = w0[i];
@@ -3433,8 +3478,9 @@ Launch make_tiled_launch(int n, int batch, int cz_tile) {
 
 Launch make_spmv_launch(int n, int batch, int elem_bytes, int cz_tile) {
     Launch L{};
-    if (n == 64 * kRowCells && elem_bytes == 4) {   // full-row form
-        const int gy = n / kRowWaves;
+    const int rh = row_waves(n, elem_bytes);
+    if (rh) {   // full-row form
+        const int gy = n / (kRowWaves / rh);
         int nz = kRowBlocks / gy;
         nz = nz < 1 ? 1 : nz;
         const int cz = (n + nz - 1) / nz;
@@ -3444,7 +3490,8 @@ Launch make_spmv_launch(int n, int batch, int elem_bytes, int cz_tile) {
         L.nblocks = L.grid.x * L.grid.y * L.grid.z;
         L.cz = cz;
         L.nz = nz;
-        L.v = kRowCells;
+        L.v = n / (64 * rh);
+        L.h = rh;
         return L;
     }
     const int TY = kTY * spmv_rows(elem_bytes);
@@ -3623,14 +3670,14 @@ static void spmv_launch(const Launch& L, const Launch& TL, hipStream_t s, const 
                         DevState* st, int k, const CgArgs<T>& a) {
 #define SPMV_ARGS st, k, a.rin, a.rout, a.diag, a.w, a.pold, a.pold2, a.pnew, a.qold, a.q, a.x, \
                   a.part_in, a.nb_in, a.part_out, a.fresh, a.maxit, a.xzero
-    if constexpr (sizeof(T) == 4) {
-        if (TL.nblocks && TL.v == kRowCells) {
-            Phys pt = ph;
-            pt.cz = TL.cz;
-            pt.nz = TL.nz;
-            LAUNCH((k_pcg_spmv_rows<T, kRowCells, XM>), TL, s, pt, SPMV_ARGS);
-            return;
-        }
+    if (TL.nblocks && TL.v) {
+        Phys pt = ph;
+        pt.cz = TL.cz;
+        pt.nz = TL.nz;
+        if (TL.v == 2 && TL.h == 1) LAUNCH((k_pcg_spmv_rows<T, 2, 1, XM>), TL, s, pt, SPMV_ARGS);
+        else if constexpr (sizeof(T) == 4) LAUNCH((k_pcg_spmv_rows<T, 4, 1, XM>), TL, s, pt, SPMV_ARGS);
+        else LAUNCH((k_pcg_spmv_rows<T, 2, 2, XM>), TL, s, pt, SPMV_ARGS);
+        return;
     }
     if (TL.nblocks) {
         Phys pt = ph;

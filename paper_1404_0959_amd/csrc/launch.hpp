@@ -17,6 +17,7 @@ struct Launch {
     int cz;             // cells per thread along z
     int nz;             // blocks per member along z
     int v = 0;          // CG kernel: cells per lane along x of the full-row form (0: tiles)
+    int h = 0;          // and wavefronts per x-row
 };
 
 constexpr int kTargetBlocks = 2048;
@@ -37,20 +38,27 @@ Launch make_launch_shaped(int n, int batch, int bx, int cz);
 // exactly min(cz_tile, n) when cz_tile > 0 (a tuned choice).
 Launch make_tiled_launch(int n, int batch = 1, int cz_tile = 0);
 
-// Launch of the CG kernel for fields of elem_bytes per value.  For
-// n = 64 kRowCells and FP32: the full-row form, blocks of kRowWaves
-// wavefronts each owning one x-row (kRowCells cells per lane), about
-// kRowBlocks blocks per member (v = kRowCells; in FP64 its registers would
-// not fit).  Otherwise, for n a multiple of 64 (and of 8 spmv_rows), tiles of
-// 64 x (8 spmv_rows) cells, 64 x 8 threads each owning spmv_rows rows (v = 0;
-// two rows in FP64 halve the tile's y halo; in FP32 two measured no faster);
-// for the other multiples of kSmallTX, tiles of kSmallTX x kSmallTX cells, one thread per
-// column (block.x = kSmallTX); nblocks is 0 when none is available.  Tiles
-// march over at least 8 planes, or exactly min(cz_tile, n) when cz_tile > 0
-// (a tuned choice; the full-row form ignores it).
+// Launch of the CG kernel for fields of elem_bytes per value.
+// * n = 128 and 256: the full-row form, blocks of kRowWaves wavefronts, about
+//   kRowBlocks blocks per member (v cells per lane, h wavefronts per row): at
+//   256 one wavefront per x-row and 4 cells per lane in FP32, two per x-row and
+//   2 cells per lane in FP64 (4 doubles per lane spill registers); at 128 one
+//   wavefront per x-row and 2 cells per lane.
+// * Other multiples of 64 (and of 8 spmv_rows): tiles of 64 x (8 spmv_rows)
+//   cells, 64 x 8 threads each owning spmv_rows rows (v = 0; two rows in FP64
+//   halve the tile's y halo; in FP32 two measured no faster).
+// * Other multiples of kSmallTX: tiles of kSmallTX x kSmallTX cells, one thread
+//   per column (block.x = kSmallTX).
+// nblocks is 0 when none is available.  Tiles march over at least 8 planes, or
+// exactly min(cz_tile, n) when cz_tile > 0 (a tuned choice; the full-row form
+// ignores it).
 constexpr int spmv_rows(int elem_bytes) { return elem_bytes == 8 ? 2 : 1; }
 constexpr int kSmallTX = 16;
-constexpr int kRowCells = 4, kRowWaves = 8, kRowBlocks = 256;
+constexpr int kRowWaves = 8, kRowBlocks = 256;
+// Wavefronts per x-row of the full-row CG form for n and elem_bytes (0: none).
+constexpr int row_waves(int n, int elem_bytes) {
+    return n == 128 ? 1 : n != 256 ? 0 : elem_bytes == 4 ? 1 : 2;
+}
 Launch make_spmv_launch(int n, int batch, int elem_bytes, int cz_tile = 0);
 
 // dst[0..count) = v (FP64).

@@ -109,7 +109,8 @@ def test_helm_apply_parity(P, ora, n):
 
 @pytest.mark.parametrize("n", [16, 40, 128, 256])
 def test_helm_solve_parity(P, ora, n):
-    """128 and 256 run the 64 x 16 tiled CG kernel (FP64, two rows per thread)."""
+    """16 runs the 16 x 16 tiled CG kernel, 40 the gathered one, 128 and 256 the
+    full-row one (FP64: one wavefront per x-row at 128, two at 256)."""
     import torch
     rng = np.random.default_rng(100 + n)
     h = 2 * math.pi / n
