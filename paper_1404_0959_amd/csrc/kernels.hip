@@ -3675,8 +3675,8 @@ static void spmv_launch(const Launch& L, const Launch& TL, hipStream_t s, const 
         pt.cz = TL.cz;
         pt.nz = TL.nz;
         if (TL.v == 2 && TL.h == 1) LAUNCH((k_pcg_spmv_rows<T, 2, 1, XM>), TL, s, pt, SPMV_ARGS);
+        else if (TL.v == 2) LAUNCH((k_pcg_spmv_rows<T, 2, 2, XM>), TL, s, pt, SPMV_ARGS);
         else if constexpr (sizeof(T) == 4) LAUNCH((k_pcg_spmv_rows<T, 4, 1, XM>), TL, s, pt, SPMV_ARGS);
-        else LAUNCH((k_pcg_spmv_rows<T, 2, 2, XM>), TL, s, pt, SPMV_ARGS);
         return;
     }
     if (TL.nblocks) {
