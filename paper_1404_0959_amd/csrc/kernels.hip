@@ -567,7 +567,10 @@ __global__ void __launch_bounds__(kTX * kTY, sizeof(T) == 4 ? 4 : 2) k_mom_sweep
         if (HBYA) {
             stream_st(w + (col + pl), ((T)(st + mem_)->rho_ref + crk) * ia);
             stream_st(p0 + (col + pl),
-                      pdev(crk, (st + mem_)->rho_ref, (st + mem_)->p_ref, ph.gamma));
+                      ph.fourier   // ideal gas at the predicted temperature T*
+                          ? (T)(((st + mem_)->rho_ref + (double)crk) * ph.R * ph.ts[col + pl] -
+                                (st + mem_)->p_ref)
+                          : pdev(crk, (st + mem_)->rho_ref, (st + mem_)->p_ref, ph.gamma));
         }
         lds_barrier();
         // advance the queues with the values loaded one plane ago, then load
@@ -847,7 +850,8 @@ __global__ void __launch_bounds__(kTX * kTY, sizeof(T) == 4 ? 4 : 2) k_corr_rhs_
         double b;
         T dgT, phf[3];
         corr_rhs_cell(wv, rv, hl, pv, cn, dt, rref, pref, gamma_psi(ph), ph.A, ph.inv_V, ph.inv_h,
-                      ph.inv_h2, b, dgT, phf);
+                      ph.inv_h2, b, dgT, phf, ph.bdf2 ? (st + mem_)->bdf : nullptr,
+                      ph.bdf2 ? ph.rm1[P] : 0.0);
         corr_rhs_store(P, N, b, dgT, phf, pref + (double)pv[0], phiH, rvec, diag, snap_b,
                        snap_diag, snap_p0, b64, v);
         // advance the queues with the values loaded one plane ago, then load
@@ -2298,6 +2302,16 @@ __device__ inline void corr_update_cell(const T (&pv)[13], const T (&fp)[3], con
     for (int m = 0; m < 3; ++m) um[m] = hb[m] - dgauss13(pv, m, inv_h) / a;
 }
 
+// BDF2's conservative density: rho_k = (c1 rho^n - c2 rho^{n-1} - dt div phi_k) / c0.
+template <typename T>
+__device__ inline T corr_rho_bdf2(const T (&fp)[3], const T (&fm)[3], T rnP, double rm1P, T dt,
+                                  double inv_V, const double* bc) {
+    double dphi = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dphi += (double)fp[d] - (double)fm[d];
+    return (T)((bc[1] * (double)rnP - bc[2] * rm1P - (double)dt * dphi * inv_V) / bc[0]);
+}
+
 template <typename T, bool LAST>
 __global__ void __launch_bounds__(kBlock) k_corr_update(Phys ph, const DevState* st,
                                                         const T* __restrict__ rn,
@@ -2324,13 +2338,7 @@ __global__ void __launch_bounds__(kBlock) k_corr_update(Phys ph, const DevState*
     loads_issued();
     T r, um[3];
     corr_update_cell(pv, fp, fm, hb, rnP, a, dt, inv_V, inv_h, r, um);
-    if (ph.bdf2) {   // rho_k = (c1 rho^n - c2 rho^{n-1} - dt div phi_k) / c0
-        const double* bc = (st + mem_)->bdf;
-        double dphi = 0.0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) dphi += (double)fp[d] - (double)fm[d];
-        r = (T)((bc[1] * (double)rnP - bc[2] * ph.rm1[P] - (double)dt * dphi * ph.inv_V) / bc[0]);
-    }
+    if (ph.bdf2) r = corr_rho_bdf2(fp, fm, rnP, ph.rm1[P], dt, ph.inv_V, (st + mem_)->bdf);
     rk[P] = r;
     double usq = 0.0;
 #pragma unroll
@@ -2350,6 +2358,21 @@ __global__ void __launch_bounds__(kBlock) k_corr_update(Phys ph, const DevState*
 
 // ---------------------------------------------------------------- dust
 // Particle-velocity correction source a = Du/Dt = (u^{n+1} - u^n)/dt + (u^{n+1}.grad)u^{n+1}.
+// BDF2's a = (c0 u^{n+1} - c1 u^n + c2 u^{n-1}) / dt + (u.grad)u, u^{n-1} at
+// um1 (components N apart).
+template <typename T>
+__device__ inline void dudt_bdf2_cell(const T (&uv)[3][13], const T (&u0)[3], const double* um1,
+                                      size_t N, size_t P, T dt, T inv_h, const double* bc,
+                                      T (&out)[3]) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const T conv = uv[0][0] * dgauss13(uv[m], 0, inv_h) + uv[1][0] * dgauss13(uv[m], 1, inv_h) +
+                       uv[2][0] * dgauss13(uv[m], 2, inv_h);
+        out[m] = (T)((bc[0] * (double)uv[m][0] - bc[1] * (double)u0[m] + bc[2] * um1[m * N + P]) /
+                     (double)dt) + conv;
+    }
+}
+
 template <typename T>
 __device__ inline void dudt_cell(const T (&uv)[3][13], const T (&u0)[3], T dt, T inv_h,
                                  T (&out)[3]) {
@@ -2379,16 +2402,7 @@ __global__ void __launch_bounds__(kBlock) k_dudt(Phys ph, const DevState* st,
     loads_issued();
     T out[3];
     dudt_cell(uv, u0, dt, inv_h, out);
-    if (ph.bdf2) {   // (c0 u^{n+1} - c1 u^n + c2 u^{n-1}) / dt + (u.grad)u
-        const double* bc = (st + mem_)->bdf;
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            const T conv = uv[0][0] * dgauss13(uv[m], 0, inv_h) + uv[1][0] * dgauss13(uv[m], 1, inv_h) +
-                           uv[2][0] * dgauss13(uv[m], 2, inv_h);
-            out[m] = (T)((bc[0] * (double)uv[m][0] - bc[1] * (double)u0[m] + bc[2] * ph.um1[m * N + P]) /
-                         (double)dt) + conv;
-        }
-    }
+    if (ph.bdf2) dudt_bdf2_cell(uv, u0, ph.um1, N, P, dt, inv_h, (st + mem_)->bdf, out);
 #pragma unroll
     for (int m = 0; m < 3; ++m) acc[m * N + P] = out[m];
     END_CELLS
@@ -2453,6 +2467,25 @@ __device__ inline T dust_sweep_cell(const T (&yv)[13], const T (&gpv)[3], const 
     return (rj / dt - off) / diag;
 }
 
+// BDF2's sweep: diagonal c0 rho^{n+1}/dt + (9/16) div G, right side
+// (c1 rho_j - c2 rho_j^{n-1})/dt.
+template <typename T>
+__device__ inline T dust_sweep_bdf2_cell(const T (&yv)[13], const T (&gpv)[3], const T (&gmv)[3],
+                                         T rj, double rjm1P, T r1P, T dt, T inv_V, double rref,
+                                         const double* bc, T& diag) {
+    T conv = T(0), dG = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        conv += gpv[d] * i4g(yv, d, 0) - gmv[d] * i4g(yv, d, -1);
+        dG += gpv[d] - gmv[d];
+    }
+    conv *= inv_V;
+    dG *= inv_V;
+    const T off = conv - T(0.5625) * dG * yv[0];
+    diag = (T)(bc[0] * (rref + (double)r1P) / (double)dt) + T(0.5625) * dG;
+    return ((T)((bc[1] * (double)rj - bc[2] * rjm1P) / (double)dt) - off) / diag;
+}
+
 // CHECK (a class's first sweep; the diagonal and G are the same in every
 // sweep): partials of max(-diagonal), so that a diagonal <= 0 anywhere is
 // flagged, and of the dust's Courant rate sum_f |G_f| / (2 rho^{n+1} V).
@@ -2477,19 +2510,9 @@ __global__ void __launch_bounds__(kBlock) k_dust_sweep(Phys ph, const DevState* 
     const T rj = rhoj[P], r1P = r1[P];
     loads_issued();
     T dg;
-    if (ph.bdf2) {   // diagonal c0 rho^{n+1}/dt + (9/16) div G, right side (c1 rho_j - c2 rho_j^{n-1})/dt
-        const double* bc = (st + mem_)->bdf;
-        T conv = T(0), dG = T(0);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            conv += gpv[d] * i4g(yv, d, 0) - gmv[d] * i4g(yv, d, -1);
-            dG += gpv[d] - gmv[d];
-        }
-        conv *= inv_V;
-        dG *= inv_V;
-        const T off = conv - T(0.5625) * dG * yv[0];
-        dg = (T)(bc[0] * (rref + (double)r1P) / (double)dt) + T(0.5625) * dG;
-        Yout[P] = ((T)((bc[1] * (double)rj - bc[2] * ph.rjm1[P]) / (double)dt) - off) / dg;
+    if (ph.bdf2) {
+        Yout[P] = dust_sweep_bdf2_cell(yv, gpv, gmv, rj, ph.rjm1[P], r1P, dt, inv_V, rref,
+                                       (st + mem_)->bdf, dg);
     } else {
         Yout[P] = dust_sweep_cell(yv, gpv, gmv, rj, r1P, dt, inv_V, (T)(st + mem_)->rho_ref, dg);
     }
@@ -2517,6 +2540,12 @@ __global__ void __launch_bounds__(kBlock) k_dust_faceflux(Phys ph, const T* __re
 // rho_j^{n+1} (mass; non-finite if any value is) and max(-rho_j^{n+1}).
 // fdo (two-way coupling): the class's own-face fluxes are added to the
 // mixture's dust flux F_d of the next step (written by the first class).
+// BDF2's conservative finish: (c1 rho_j - c2 rho_j^{n-1} - dt div F) / c0.
+template <typename T>
+__device__ inline T dust_finish_bdf2(T rj, double rjm1P, T dt, T dF, T inv_V, const double* bc) {
+    return (T)((bc[1] * (double)rj - bc[2] * rjm1P - (double)(dt * dF * inv_V)) / bc[0]);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dust_finish(Phys ph, const DevState* st,
                                                         const T* __restrict__ rhoj,
@@ -2534,10 +2563,8 @@ __global__ void __launch_bounds__(kBlock) k_dust_finish(Phys ph, const DevState*
     if (fdo)
 #pragma unroll
         for (int d = 0; d < 3; ++d) fdo[d * N + P] = (first ? T(0) : fdo[d * N + P]) + F[d * N + P];
-    const T out = ph.bdf2   // (c1 rho_j - c2 rho_j^{n-1} - dt div F) / c0
-                      ? (T)(((st + mem_)->bdf[1] * (double)rhoj[P] - (st + mem_)->bdf[2] * ph.rjm1[P] -
-                             (double)(dt * dF * inv_V)) / (st + mem_)->bdf[0])
-                      : rhoj[P] - dt * dF * inv_V;
+    const T out = ph.bdf2 ? dust_finish_bdf2(rhoj[P], ph.rjm1[P], dt, dF, inv_V, (st + mem_)->bdf)
+                          : rhoj[P] - dt * dF * inv_V;
     rhoj1[P] = out;
     v[0] += (double)out;
     v[1] = fmax(v[1], -(double)out);
@@ -3021,6 +3048,8 @@ struct TiledMomSource : TiledBase<T> {
     const T *rn, *un;
     T* src;
     T dt, m3, inv_h, rref;
+    // BDF2: the coefficients and the state at t^{n-1}
+    const double *bc, *rm1, *um1;
     struct Pts { T rn, u[3]; };
     __device__ void member(const Phys& ph, const DevState* d) {
         this->NT = ph.NT;
@@ -3028,6 +3057,9 @@ struct TiledMomSource : TiledBase<T> {
         m3 = (T)(ph.mu / 3.0);
         inv_h = (T)ph.inv_h;
         rref = (T)d->rho_ref;
+        bc = ph.bdf2 ? d->bdf : nullptr;
+        rm1 = ph.rm1;
+        um1 = ph.um1;
     }
     __device__ Pts load(size_t P) const {
         return {stream_ld(rn + P),
@@ -3037,7 +3069,15 @@ struct TiledMomSource : TiledBase<T> {
     __device__ void cell(size_t P, const T (&v)[1][13], const T (&)[3], const T (&)[3],
                          const Pts& p, double*) const {
         T out[3];
-        mom_source_cell(v[0], p.u, rref + p.rn, dt, m3, inv_h, out);
+        const T rho = rref + p.rn;
+        mom_source_cell(v[0], p.u, rho, dt, m3, inv_h, out);
+        if (bc) {   // as k_mom_source
+            const double rm = (double)rref + rm1[P];
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+                out[m] = (T)((bc[1] * (double)rho * (double)p.u[m] - bc[2] * rm * um1[m * this->NT + P]) /
+                             (double)dt + (double)m3 * (double)dgauss13(v[0], m, inv_h));
+        }
 #pragma unroll
         for (int m = 0; m < 3; ++m) stream_st(src + (m * this->NT + P), out[m]);
     }
@@ -3089,6 +3129,8 @@ struct TiledCorrUpdate : TiledBase<T> {
     T *rk, *u;
     T dt, inv_V, inv_h;
     double rref;
+    const double *bc, *rm1;   // BDF2: the coefficients and rho at t^{n-1}
+    double inv_Vd;
     struct Pts { T hb[3], rn, a; };
     __device__ void member(const Phys& ph, const DevState* d) {
         this->NT = ph.NT;
@@ -3096,6 +3138,9 @@ struct TiledCorrUpdate : TiledBase<T> {
         inv_V = (T)ph.inv_V;
         inv_h = (T)ph.inv_h;
         rref = d->rho_ref;
+        bc = ph.bdf2 ? d->bdf : nullptr;
+        rm1 = ph.rm1;
+        inv_Vd = ph.inv_V;
     }
     __device__ void init(double* acc) const {
         acc[0] = 0.0;
@@ -3113,6 +3158,7 @@ struct TiledCorrUpdate : TiledBase<T> {
                          const Pts& p, double* acc) const {
         T r, um[3];
         corr_update_cell(v[0], fp, fm, p.hb, p.rn, p.a, dt, inv_V, inv_h, r, um);
+        if (bc) r = corr_rho_bdf2(fp, fm, p.rn, rm1[P], dt, inv_Vd, bc);
         stream_st(rk + P, r);
         double usq = 0.0;
 #pragma unroll
@@ -3175,11 +3221,14 @@ struct TiledDudt : TiledBase<T> {
     const T* un;
     T* acc_out;
     T dt, inv_h;
+    const double *bc, *um1;   // BDF2: the coefficients and u at t^{n-1}
     struct Pts { T u0[3]; };
     __device__ void member(const Phys& ph, const DevState* d) {
         this->NT = ph.NT;
         dt = (T)d->dt;
         inv_h = (T)ph.inv_h;
+        bc = ph.bdf2 ? d->bdf : nullptr;
+        um1 = ph.um1;
     }
     __device__ Pts load(size_t P) const {
         return {{stream_ld(un + P), stream_ld(un + this->NT + P), stream_ld(un + 2 * this->NT + P)}};
@@ -3187,7 +3236,8 @@ struct TiledDudt : TiledBase<T> {
     __device__ void cell(size_t P, const T (&v)[3][13], const T (&)[3], const T (&)[3],
                          const Pts& p, double*) const {
         T out[3];
-        dudt_cell(v, p.u0, dt, inv_h, out);
+        if (bc) dudt_bdf2_cell(v, p.u0, um1, this->NT, P, dt, inv_h, bc, out);
+        else dudt_cell(v, p.u0, dt, inv_h, out);
 #pragma unroll
         for (int m = 0; m < 3; ++m) stream_st(acc_out + (m * this->NT + P), out[m]);
     }
@@ -3241,12 +3291,17 @@ struct TiledDustSweep : TiledBase<T> {
     T* Yout;
     T dt, inv_V, rref;
     double Vc;
+    const double *bc, *rjm1;   // BDF2: the coefficients and the class's rho_j at t^{n-1}
+    double rrefd;
     struct Pts { T rj, r1; };
     __device__ void member(const Phys& ph, const DevState* d) {
         dt = (T)d->dt;
         inv_V = (T)ph.inv_V;
         rref = (T)d->rho_ref;
         Vc = ph.V;
+        bc = ph.bdf2 ? d->bdf : nullptr;
+        rjm1 = ph.rjm1;
+        rrefd = d->rho_ref;
     }
     __device__ Pts load(size_t P) const { return {stream_ld(rhoj + P), stream_ld(r1 + P)}; }
     __device__ void init(double* acc) const {
@@ -3256,7 +3311,9 @@ struct TiledDustSweep : TiledBase<T> {
     __device__ void cell(size_t P, const T (&v)[1][13], const T (&fp)[3], const T (&fm)[3],
                          const Pts& p, double* acc) const {
         T dg;
-        stream_st(Yout + P, dust_sweep_cell(v[0], fp, fm, p.rj, p.r1, dt, inv_V, rref, dg));
+        stream_st(Yout + P, bc ? dust_sweep_bdf2_cell(v[0], fp, fm, p.rj, rjm1[P], p.r1, dt, inv_V,
+                                                      rrefd, bc, dg)
+                               : dust_sweep_cell(v[0], fp, fm, p.rj, p.r1, dt, inv_V, rref, dg));
         if (CHECK) {
             acc[0] = fmax(acc[0], -(double)dg);
             acc[1] = fmax(acc[1], courant_rate(fp, fm, p.r1, (double)rref, Vc));
@@ -3281,11 +3338,14 @@ struct TiledDustFinish : TiledBase<T> {
     T* fdo;        // two-way coupling: the dust flux F_d of the next step (as k_dust_finish)
     int first_cls;
     T dt, inv_V;
+    const double *bc, *rjm1;   // BDF2: the coefficients and the class's rho_j at t^{n-1}
     struct Pts { T rj; };
     __device__ void member(const Phys& ph, const DevState* d) {
         this->NT = ph.NT;
         dt = (T)d->dt;
         inv_V = (T)ph.inv_V;
+        bc = ph.bdf2 ? d->bdf : nullptr;
+        rjm1 = ph.rjm1;
     }
     __device__ Pts load(size_t P) const { return {stream_ld(rhoj + P)}; }
     __device__ void init(double* acc) const {
@@ -3303,7 +3363,7 @@ struct TiledDustFinish : TiledBase<T> {
                 T* q = fdo + (d * this->NT + P);
                 *q = (first_cls ? T(0) : *q) + fp[d] * i4g(v[0], d, 0);
             }
-        const T out = p.rj - dt * dF * inv_V;
+        const T out = bc ? dust_finish_bdf2(p.rj, rjm1[P], dt, dF, inv_V, bc) : p.rj - dt * dF * inv_V;
         stream_st(rhoj1 + P, out);
         acc[0] += (double)out;
         acc[1] = fmax(acc[1], -(double)out);
@@ -3330,6 +3390,8 @@ struct TiledCorrFluxUpdate : TiledBase<T> {
     double* snap_x;
     T A, inv_h, dt, inv_V;
     double rref, V;
+    const double *bc, *rm1;   // BDF2: the coefficients and rho at t^{n-1}
+    double inv_Vd;
     struct Pts { T hb[3], rn, a; };
     __device__ void member(const Phys& ph, const DevState* d) {
         this->NT = ph.NT;
@@ -3339,6 +3401,9 @@ struct TiledCorrFluxUpdate : TiledBase<T> {
         inv_V = (T)ph.inv_V;
         rref = d->rho_ref;
         V = ph.V;
+        bc = ph.bdf2 ? d->bdf : nullptr;
+        rm1 = ph.rm1;
+        inv_Vd = ph.inv_V;
     }
     __device__ void init(double* acc) const {
         acc[0] = 0.0;
@@ -3369,6 +3434,7 @@ struct TiledCorrFluxUpdate : TiledBase<T> {
         if (snap_x) snap_x[P] = (double)v[2][0];
         T r, um[3];
         corr_update_cell(pv, fp, fm, p.hb, p.rn, p.a, dt, inv_V, inv_h, r, um);
+        if (bc) r = corr_rho_bdf2(fp, fm, p.rn, rm1[P], dt, inv_Vd, bc);
         stream_st(rk + P, r);
         double usq = 0.0;
 #pragma unroll
@@ -3402,6 +3468,10 @@ struct TiledPredict : TiledBase<T> {
     T *rs, *aP, *divu, *pn;
     double dtd, sigma, pref, gamma;
     T dt, inv_V, inv_h, diag_visc, rref;
+    // variants: the ideal gas at T^n (Fourier), the BDF2 coefficients
+    const double *tn, *rm1;
+    double R, bc[3];
+    bool fourier, bdf2;
     struct Pts { T rn; };
     __device__ void member(const Phys& ph, const DevState* d) {
         double sg[1];
@@ -3415,6 +3485,14 @@ struct TiledPredict : TiledBase<T> {
         rref = (T)d->rho_ref;
         pref = d->p_ref;
         gamma = ph.gamma;
+        fourier = ph.fourier;
+        bdf2 = ph.bdf2;
+        tn = ph.tn;
+        rm1 = ph.rm1;
+        R = ph.R;
+        bc[0] = bc[1] = 1.0;
+        bc[2] = 0.0;
+        if (bdf2) bdf2_coef(dtd, d->dt_prev, bc);
     }
     __device__ Pts load(size_t P) const { return {stream_ld(rn + P)}; }
     __device__ void cell(size_t P, const T (&v)[3][13], const T (&fp)[3], const T (&fm)[3],
@@ -3424,6 +3502,16 @@ struct TiledPredict : TiledBase<T> {
         for (int d = 0; d < 3; ++d) cross_line(v[d], d, ul[d]);
         T r, a, dv, pp;
         predict_cell(fp, fm, ul, p.rn, dt, inv_V, inv_h, diag_visc, rref, pref, gamma, r, a, dv, pp);
+        if (fourier) pp = (T)(((double)rref + (double)p.rn) * R * tn[P] - pref);
+        if (bdf2) {   // as k_predict
+            double dphi = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) dphi += (double)fp[d] - (double)fm[d];
+            dphi *= (double)inv_V;
+            const double rr = (bc[1] * (double)p.rn - bc[2] * rm1[P] - dtd * dphi) / bc[0];
+            r = (T)rr;
+            a = (T)(bc[0] * ((double)rref + rr) / dtd + 0.5625 * dphi + (double)diag_visc);
+        }
         stream_st(rs + P, r);
         stream_st(aP + P, a);
         stream_st(divu + P, dv);
@@ -3433,6 +3521,8 @@ struct TiledPredict : TiledBase<T> {
         if (!(dtd > 0.0) || !isfinite(dtd)) d->flags |= 16;  // bad dt
         d->sigma = sigma;
         d->dt = dtd;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) d->bdf[q] = bc[q];
     }
 };
 

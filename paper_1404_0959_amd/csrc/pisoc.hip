@@ -626,33 +626,6 @@ CgVecs<T> cg_vecs(const StepPtrs<T>& S) {
     return v;
 }
 
-// The launch of a field kernel: the tiled z-march, or none (the gathered
-// form) where the step's variant changes that kernel's arithmetic and its
-// tiled form does not carry the change: the Fourier closure the predictor's
-// p^n and the HbyA pass's p0 (the corrector set-up takes psi from p0 in either
-// form); BDF2 every kernel with a time derivative.  The momentum sweeps, the
-// flux correction and the dust fluxes stay tiled in every variant.
-enum TlKernel {
-    TK_PREDICT, TK_MOM_SOURCE, TK_MOM_SWEEP, TK_HBYA, TK_CORR_RHS, TK_CORR_FLUX,
-    TK_CORR_UPDATE, TK_DUDT, TK_DUST_FLUX, TK_DUST_SWEEP, TK_DUST_FINISH
-};
-const Launch& tl(const pisoc_ctx* ctx, TlKernel k) {
-    static const Launch none{};
-    bool gathered = false;
-    switch (k) {
-    case TK_PREDICT: gathered = ctx->ph.fourier || ctx->ph.bdf2; break;
-    case TK_HBYA: gathered = ctx->ph.fourier; break;
-    case TK_MOM_SOURCE:
-    case TK_CORR_RHS:
-    case TK_CORR_UPDATE:
-    case TK_DUDT:
-    case TK_DUST_SWEEP:
-    case TK_DUST_FINISH: gathered = ctx->ph.bdf2; break;
-    default: break;
-    }
-    return gathered ? none : ctx->TL;
-}
-
 // dt, density predictor, momentum source and predictor sweeps (u* ends in
 // the u slot ctx->ucur_slot).
 // cfl_ready: the Courant partials of the current state are already in PS_CFL.
@@ -671,11 +644,11 @@ pisoc_status enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
         ctx->cfl_part = ctx->part(PS_CFL);
     }
     timed(ctx, KC_PREDICT, 11, -1, [&] {
-        O::predict(L, tl(ctx, TK_PREDICT), s, ph, st, ctx->cfl_part, ctx->nb_cfl, p.dt_fixed, p.cfl,
+        O::predict(L, ctx->TL, s, ph, st, ctx->cfl_part, ctx->nb_cfl, p.dt_fixed, p.cfl,
                    p.dt_growth, p.dt_max, S.rn, S.un, S.phin, S.rk, S.aP, S.divu, S.pn);
     });
     timed(ctx, KC_MOM_SOURCE, 8, -1,
-          [&] { O::mom_source(L, tl(ctx, TK_MOM_SOURCE), s, ph, st, S.rn, S.un, S.divu, S.src); });
+          [&] { O::mom_source(L, ctx->TL, s, ph, st, S.rn, S.un, S.divu, S.src); });
     if (p.two_way) {
         // words: rho^n, u^n x3, rho_j x K, phi x3, F_d x3, a_P and s x3 read;
         // F_m x3, a_P, s x3 written
@@ -717,7 +690,7 @@ pisoc_status enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
         for (int i = 0; i < p.n_mom_sweeps; ++i) {
             T* uout = (i & 1) ? S.ub : S.ua;
             timed(ctx, KC_MOM_SWEEP, 14, -1,
-                  [&] { O::mom_sweep(L, tl(ctx, TK_MOM_SWEEP), s, ph, st, uin, uout, S.mflux, S.aP, S.src, S.pn); });
+                  [&] { O::mom_sweep(L, ctx->TL, s, ph, st, uin, uout, S.mflux, S.aP, S.src, S.pn); });
             uin = uout;
         }
     }
@@ -754,11 +727,11 @@ void enqueue_corr_setup(pisoc_ctx* ctx, StepPtrs<T>& S, int corr, bool guess) {
     const bool f32 = sizeof(T) == sizeof(float);
     T* ucur = ucur_of(ctx, S);
     timed(ctx, KC_HBYA, 16, -1,
-          [&] { O::hbya(L, tl(ctx, TK_HBYA), s, ph, ctx->st, ucur, S.hb, S.mflux, S.aP, S.src, S.rk, S.w, S.p0); });
+          [&] { O::hbya(L, ctx->TL, s, ph, ctx->st, ucur, S.hb, S.mflux, S.aP, S.src, S.rk, S.w, S.p0); });
     const bool cap = S.snap && corr == 0;
     if (cap) O::cast_out(s, S.w, S.snap + 4 * N, N, 0.0);   // the operator's w = rho/a_P
     timed(ctx, KC_CORR_RHS, f32 ? 14 : 12, -1, [&] {
-        ctx->nb_start = O::corr_rhs(L, tl(ctx, TK_CORR_RHS), s, ph, ctx->st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH,
+        ctx->nb_start = O::corr_rhs(L, ctx->TL, s, ph, ctx->st, S.rn, S.rk, S.w, S.hb, S.p0, S.phiH,
                                     S.r, S.dg, ctx->part(PS_U), cap ? S.snap : nullptr,
                                     cap ? S.snap + N : nullptr, cap ? S.snap + 2 * N : nullptr,
                                     S.b64);
@@ -792,7 +765,7 @@ void enqueue_corr_finish(pisoc_ctx* ctx, StepPtrs<T>& S, int corr) {
     const bool cap = S.snap && corr == 0;
     T* ucur = ucur_of(ctx, S);
     const bool last = corr == ctx->prm.n_corr - 1;
-    if (tl(ctx, TK_CORR_UPDATE).nblocks) {
+    if (ctx->TL.nblocks) {
         // flux correction and update in one tiled pass (words: w, p0, p', phiH x3,
         // HbyA x3, rho^n, a_P read; phi x3, rho_k, u x3 written)
         timed(ctx, KC_CORR_UPDATE, 18, -1, [&] {
@@ -805,11 +778,11 @@ void enqueue_corr_finish(pisoc_ctx* ctx, StepPtrs<T>& S, int corr) {
         return;
     }
     timed(ctx, KC_CORR_FLUX, 10, -1, [&] {
-        O::corr_flux(L, tl(ctx, TK_CORR_FLUX), s, ph, ctx->st, S.p0, S.x, S.w, S.phiH, S.phik, S.q,
+        O::corr_flux(L, ctx->TL, s, ph, ctx->st, S.p0, S.x, S.w, S.phiH, S.phik, S.q,
                      cap ? S.snap + 3 * N : nullptr);
     });
     timed(ctx, KC_CORR_UPDATE, 13, -1, [&] {
-        ctx->nb_mass = O::corr_update(L, tl(ctx, TK_CORR_UPDATE), s, ph, ctx->st, last, S.rn, S.phik, S.hb, S.q,
+        ctx->nb_mass = O::corr_update(L, ctx->TL, s, ph, ctx->st, last, S.rn, S.phik, S.hb, S.q,
                                       S.aP, S.rk, ucur, ctx->part(PS_MASS));
     });
 }
@@ -827,10 +800,10 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
     const size_t N = ctx->NT();
     T* ucur = ucur_of(ctx, S);
     if (p.n_classes > 0) {
-        timed(ctx, KC_DUDT, 9, -1, [&] { O::dudt(L, tl(ctx, TK_DUDT), s, ph, st, S.un, ucur, S.acc); });
+        timed(ctx, KC_DUDT, 9, -1, [&] { O::dudt(L, ctx->TL, s, ph, st, S.un, ucur, S.acc); });
         for (int c = 0; c < p.n_classes; ++c) {
             timed(ctx, KC_DUST_FLUX, 13, -1, [&] {
-                O::dust_flux(L, tl(ctx, TK_DUST_FLUX), s, ph, st, c, S.phik, S.rk, S.acc, S.G, S.rj + c * N, S.rn,
+                O::dust_flux(L, ctx->TL, s, ph, st, c, S.phik, S.rk, S.acc, S.G, S.rj + c * N, S.rn,
                              S.Ya);
             });
             T* yin = S.Ya;
@@ -842,17 +815,17 @@ void enqueue_dust(pisoc_ctx* ctx, StepPtrs<T>& S) {
                 double* chk = i == 0 ? ctx->part(PS_DDIAG + 2 * c) : nullptr;
                 timed(ctx, KC_DUST_SWEEP, 7, -1, [&] {
                     const unsigned nb =
-                        O::dust_sweep(L, tl(ctx, TK_DUST_SWEEP), s, phc, st, yin, yout, S.G, S.rj + c * N, S.rk, chk);
+                        O::dust_sweep(L, ctx->TL, s, phc, st, yin, yout, S.G, S.rj + c * N, S.rk, chk);
                     if (chk) nb_diag = nb;
                 });
                 std::swap(yin, yout);
             }
             // two-way coupling: the class's face fluxes add up to the next step's F_d
             const double fdw = S.fdk ? (c == 0 ? 3.0 : 6.0) : 0.0;
-            if (tl(ctx, TK_DUST_FINISH).nblocks) {
+            if (ctx->TL.nblocks) {
                 // face fluxes and finish in one tiled pass (words: Y, G, rho_j read, rho_j' written)
                 timed(ctx, KC_DUST_FINISH, 6 + fdw, -1, [&] {
-                    nb_dust = O::dust_finish_fused(ctx->TL, s, ph, st, yin, S.G, S.rj + c * N,
+                    nb_dust = O::dust_finish_fused(ctx->TL, s, phc, st, yin, S.G, S.rj + c * N,
                                                    S.rj1 + c * N, ctx->part(PS_DUST + 2 * c),
                                                    S.fdk, c == 0);
                 });
@@ -1293,8 +1266,7 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     ctx->TS = make_spmv_launch(prm->n, batch, prm->precision == PISOC_FP64 ? 8 : 4);
     // PISOC_UNTILED=1 selects the untiled kernels (kernel-comparison tests)
     if (const char* e = std::getenv("PISOC_UNTILED"); e && e[0] == '1') ctx->TL = ctx->TS = Launch{};
-    // (the Fourier closure and BDF2 run the gathered form of the kernels they
-    // change: see tl())
+    // (the tiled forms carry the Fourier closure and BDF2 as the gathered ones)
     ctx->L = make_launch(prm->n, batch);
     ctx->ph = make_phys(prm, ctx->L, batch);
     ctx->st = reinterpret_cast<DevState*>(ctx->ws + lay.state);
