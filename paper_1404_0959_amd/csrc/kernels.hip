@@ -1758,7 +1758,7 @@ __global__ void __launch_bounds__(kBlock) k_psidt_of(int n, double inv_h2,
     }
 }
 
-// ---- Fourier closure: the energy predictor (gathered; FP64 runs only) ----
+// ---- Fourier closure: the energy predictor (FP64 runs only; the sweep's tiled form is TiledEnergySweep) ----
 // The internal energy c_v T of the gas, discretised like the momentum
 // predictor (backward Euler, I4 convection with the old fluxes split into the
 // diagonal (9/16) div(phi) and the rest, compact Laplacian for the heat flux
@@ -1959,13 +1959,14 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_bicg_half(Phys ph, DevState* st, int i,
                                                       const T* __restrict__ r, const T* __restrict__ vv,
                                                       T* __restrict__ s, T* __restrict__ z,
-                                                      const T* __restrict__ aP, const double* part_v) {
+                                                      const T* __restrict__ aP, const double* part_v,
+                                                      unsigned nb_v) {
     MEMBER(ph)
     BicgState& g = (st + mem_)->bicg;
     if (i - 1 >= g.it_stop) return;
     const size_t N = ncell(ph);
     double rv[1];
-    reduce_member<1, 0u>(part_v, num_blocks(), ph.batch, mem_, rv);
+    reduce_member<1, 0u>(part_v, nb_v, ph.batch, mem_, rv);
     const double alpha = g.rho / rv[0];
     if (MEMBER_FIRST()) g.alpha = alpha;
     FOR_CELLS(ph)
@@ -1986,13 +1987,14 @@ __global__ void __launch_bounds__(kBlock) k_bicg_update(Phys ph, DevState* st, i
                                                         const T* __restrict__ y, const T* __restrict__ z,
                                                         const T* __restrict__ s, const T* __restrict__ tt,
                                                         T* __restrict__ r, const T* __restrict__ rh,
-                                                        const double* part_ts, double* part_res) {
+                                                        const double* part_ts, unsigned nb_ts,
+                                                        double* part_res) {
     MEMBER(ph)
     BicgState& g = (st + mem_)->bicg;
     if (i - 1 >= g.it_stop) return;
     const size_t N = ncell(ph);
     double ts[2];
-    reduce_member<2, 0u>(part_ts, num_blocks(), ph.batch, mem_, ts);
+    reduce_member<2, 0u>(part_ts, nb_ts, ph.batch, mem_, ts);
     const double omega = ts[1] > 0.0 ? ts[0] / ts[1] : 0.0;
     const double alpha = g.alpha;
     if (MEMBER_FIRST()) {
@@ -2843,6 +2845,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_tiled(Phys ph, DevState* st, K ke
     const size_t N = ncell(ph);
     K k = kern;
     k.member(ph, st + mem_);
+    if (k.skip(st + mem_)) return;   // whole block, before any barrier
     const int n = ph.n, cz = ph.cz;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kTX * ty;
     const int i0 = bp_.x * kTX, j0 = bp_.y * kTY;
@@ -3039,6 +3042,8 @@ struct TiledBase {
     size_t NT = 0;
     __device__ void init(double* acc) const { acc[0] = 0.0; }
     __device__ void first(DevState*) const {}
+    // true: the member has nothing to do in this launch (a solve already stopped)
+    __device__ bool skip(const DevState*) const { return false; }
 };
 
 template <typename T>
@@ -3453,6 +3458,89 @@ struct TiledCorrFluxUpdate : TiledBase<T> {
     }
 };
 
+// The momentum operator of the BiCGStab predictor, as k_bicg_apply: out = A y
+// for the three components, partials (w, out) and with NR = 2 (out, out);
+// nothing to do once the member's solve has stopped before iteration it.
+template <typename T, int NR_>
+struct TiledBicgApply : TiledBase<T> {
+    static constexpr int NS = 3;          // y
+    static constexpr bool FACES = true;   // F, the predictor's face fluxes
+    static constexpr int NR = NR_;
+    const T* sf[3];
+    const T *aP, *w;
+    T* out;
+    int it;
+    double inv_V, mu_h2;
+    struct Pts { T a, w[3]; };
+    __device__ void member(const Phys& ph, const DevState*) {
+        this->NT = ph.NT;
+        inv_V = ph.inv_V;
+        mu_h2 = ph.mu * ph.inv_h2;
+    }
+    __device__ bool skip(const DevState* d) const { return it - 1 >= d->bicg.it_stop; }
+    __device__ void init(double* acc) const {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    }
+    __device__ Pts load(size_t P) const {
+        return {stream_ld(aP + P),
+                {stream_ld(w + P), stream_ld(w + this->NT + P), stream_ld(w + 2 * this->NT + P)}};
+    }
+    __device__ void cell(size_t P, const T (&v)[3][13], const T (&fp)[3], const T (&fm)[3],
+                         const Pts& p, double* acc) const {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const double yP = (double)v[m][0];
+            double conv = 0.0, dF = 0.0, nb = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double f1 = (double)fp[d], f0 = (double)fm[d];
+                const double ym2 = (double)g13(v[m], d, -2), ym1 = (double)g13(v[m], d, -1),
+                             yp1 = (double)g13(v[m], d, 1), yp2 = (double)g13(v[m], d, 2);
+                conv += f1 * ((9.0 * (yP + yp1) - (ym1 + yp2)) * 0.0625) -
+                        f0 * ((9.0 * (ym1 + yP) - (ym2 + yp1)) * 0.0625);
+                dF += f1 - f0;
+                nb += yp1 + ym1;
+            }
+            const double a = (double)p.a * yP + conv * inv_V - 0.5625 * dF * inv_V * yP - mu_h2 * nb;
+            stream_st(out + (m * this->NT + P), (T)a);
+            acc[0] += (double)p.w[m] * a;
+            if (NR == 2) acc[NR - 1] += a * a;
+        }
+    }
+};
+
+// One Jacobi sweep of the Fourier closure's energy predictor, as
+// k_energy_sweep (FP64 fields; T = double).
+template <typename T>
+struct TiledEnergySweep : TiledBase<T> {
+    static constexpr int NS = 1;          // T^in
+    static constexpr bool FACES = true;   // phi^n
+    const T* sf[1];
+    const double *aT, *sT;
+    double* tout;
+    double cv, kh2, inv_V;
+    struct Pts { double a, s; };
+    __device__ void member(const Phys& ph, const DevState*) {
+        cv = ph.cv;
+        kh2 = ph.kappa * ph.inv_h2;
+        inv_V = ph.inv_V;
+    }
+    __device__ Pts load(size_t P) const { return {stream_ld(aT + P), stream_ld(sT + P)}; }
+    __device__ void cell(size_t P, const T (&v)[1][13], const T (&fp)[3], const T (&fm)[3],
+                         const Pts& p, double*) const {
+        double conv = 0.0, nb = 0.0, dphi = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            conv += (double)fp[d] * i4g(v[0], d, 0) - (double)fm[d] * i4g(v[0], d, -1);
+            nb += g13(v[0], d, 1) + g13(v[0], d, -1);
+            dphi += (double)fp[d] - (double)fm[d];
+        }
+        const double off = cv * (conv * inv_V - 0.5625 * (dphi * inv_V) * v[0][0]) - kh2 * nb;
+        stream_st(tout + P, (p.s - off) / p.a);
+    }
+};
+
 // The predictor: dt from the Courant partials (every block reduces them, as
 // k_predict), then predict_cell; the member's first thread stores dt.
 template <typename T>
@@ -3803,15 +3891,35 @@ void Ops<T>::bicg_init(const Launch& L, hipStream_t s, const Phys& ph, DevState*
     LAUNCH(k_bicg_init<T>, L, s, ph, st, x, F, aP, src, pn, r, rh, part);
 }
 template <typename T>
-void Ops<T>::bicg_iter(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int i,
-                       double tol2, int maxit, T* x, T* r, const T* rh, T* const w[6], const T* F,
-                       const T* aP, double* part_res, double* part_v, double* part_ts) {
+void Ops<T>::bicg_iter(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                       DevState* st, int i, double tol2, int maxit, T* x, T* r, const T* rh,
+                       T* const w[6], const T* F, const T* aP, double* part_res, double* part_v,
+                       double* part_ts) {
     T *p = w[0], *v = w[1], *y = w[2], *sv = w[3], *z = w[4], *tv = w[5];
+    // the stencil applications tiled where available (their partials then come
+    // from TL.nblocks blocks)
+    auto apply = [&](const T* yin, T* out, const T* wv, double* part, bool two) -> unsigned {
+        if (TL.nblocks) {
+            auto run = [&](auto k) {
+                for (int m = 0; m < 3; ++m) k.sf[m] = yin + (size_t)m * ph.NT;
+                k.face = F;
+                k.aP = aP;
+                k.w = wv;
+                k.out = out;
+                k.it = i;
+                k.part = part;
+                return tiled_launch<T>(TL, s, ph, st, k);
+            };
+            return two ? run(TiledBicgApply<T, 2>{}) : run(TiledBicgApply<T, 1>{});
+        }
+        LAUNCH(k_bicg_apply<T>, L, s, ph, st, i, two ? 1 : 0, yin, out, F, aP, wv, part);
+        return L.nblocks;
+    };
     LAUNCH(k_bicg_dir<T>, L, s, ph, st, i, tol2, maxit, r, p, v, y, aP, part_res);
-    LAUNCH(k_bicg_apply<T>, L, s, ph, st, i, 0, y, v, F, aP, rh, part_v);
-    LAUNCH(k_bicg_half<T>, L, s, ph, st, i, r, v, sv, z, aP, part_v);
-    LAUNCH(k_bicg_apply<T>, L, s, ph, st, i, 1, z, tv, F, aP, sv, part_ts);
-    LAUNCH(k_bicg_update<T>, L, s, ph, st, i, x, y, z, sv, tv, r, rh, part_ts, part_res);
+    const unsigned nb_v = apply(y, v, rh, part_v, false);
+    LAUNCH(k_bicg_half<T>, L, s, ph, st, i, r, v, sv, z, aP, part_v, nb_v);
+    const unsigned nb_ts = apply(z, tv, sv, part_ts, true);
+    LAUNCH(k_bicg_update<T>, L, s, ph, st, i, x, y, z, sv, tv, r, rh, part_ts, nb_ts, part_res);
 }
 template <typename T>
 void Ops<T>::energy_setup(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
@@ -3820,9 +3928,21 @@ void Ops<T>::energy_setup(const Launch& L, hipStream_t s, const Phys& ph, const 
     LAUNCH(k_energy_setup<T>, L, s, ph, st, rn, rs, phi, divu, pn, aT, sT);
 }
 template <typename T>
-void Ops<T>::energy_sweep(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                          const double* tin, double* tout, const T* phi, const double* aT,
-                          const double* sT) {
+void Ops<T>::energy_sweep(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                          const DevState* st, const double* tin, double* tout, const T* phi,
+                          const double* aT, const double* sT) {
+    if constexpr (sizeof(T) == sizeof(double)) {
+        if (TL.nblocks) {
+            TiledEnergySweep<T> k{};
+            k.sf[0] = tin;
+            k.face = phi;
+            k.aT = aT;
+            k.sT = sT;
+            k.tout = tout;
+            tiled_launch<T>(TL, s, ph, st, k);
+            return;
+        }
+    }
     LAUNCH(k_energy_sweep<T>, L, s, ph, st, tin, tout, phi, aT, sT);
 }
 void fill_value(hipStream_t s, double* dst, size_t count, double v) {

@@ -170,16 +170,17 @@ struct Ops {
     static void bicg_init(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, const T* x,
                           const T* F, const T* aP, const T* src, const T* pn, T* r, T* rh,
                           double* part);
-    static void bicg_iter(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int i,
-                          double tol2, int maxit, T* x, T* r, const T* rh, T* const w[6], const T* F,
-                          const T* aP, double* part_res, double* part_v, double* part_ts);
+    static void bicg_iter(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                          DevState* st, int i, double tol2, int maxit, T* x, T* r, const T* rh,
+                          T* const w[6], const T* F, const T* aP, double* part_res, double* part_v,
+                          double* part_ts);
     // Fourier closure: the energy predictor's coefficients and one Jacobi sweep
     static void energy_setup(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
                              const T* rn, const T* rs, const T* phi, const T* divu, const T* pn,
                              double* aT, double* sT);
-    static void energy_sweep(const Launch& L, hipStream_t s, const Phys& ph, const DevState* st,
-                             const double* tin, double* tout, const T* phi, const double* aT,
-                             const double* sT);
+    static void energy_sweep(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                             const DevState* st, const double* tin, double* tout, const T* phi,
+                             const double* aT, const double* sT);
     // CG preconditioned by a Chebyshev polynomial (stand-alone solve): the
     // interval's lower end, then per iteration the residual/preconditioner and
     // the direction/operator launches

@@ -677,7 +677,7 @@ pisoc_status enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
         const double tol2 = p.mom_tol * p.mom_tol;
         for (int i = 1;; i += 8) {
             for (int k = i; k < i + 8; ++k)
-                O::bicg_iter(L, s, ph, st, k, tol2, p.mom_maxit, x, r, rh, wk, S.mflux, S.aP, pres,
+                O::bicg_iter(L, ctx->TL, s, ph, st, k, tol2, p.mom_maxit, x, r, rh, wk, S.mflux, S.aP, pres,
                              ctx->part(PS_CG + kBicgV), ctx->part(PS_CG + kBicgTs));
             pisoc_status ss = sync_state(ctx);
             if (ss != PISOC_OK) return ss;
@@ -707,7 +707,7 @@ pisoc_status enqueue_front(pisoc_ctx* ctx, StepPtrs<T>& S, bool cfl_ready) {
         const double* tin = ph.tn;
         for (int i = 0; i < p.n_mom_sweeps; ++i) {
             double* tout = ((p.n_mom_sweeps - 1 - i) & 1) ? tw : tk;
-            O::energy_sweep(L, s, ph, st, tin, tout, S.phin, aT, sT);
+            O::energy_sweep(L, ctx->TL, s, ph, st, tin, tout, S.phin, aT, sT);
             tin = tout;
         }
     }
