@@ -125,14 +125,14 @@ __global__ void __launch_bounds__(256) k_conv(int n, int batch, const uint16_t* 
     }
 }
 
-// Tiles of the first and last layers: a wavefront owns 16 cells along x of a
-// block of kRY x kRZ output rows (y, z) and walks the (kRY + 2) x (kRZ + 2)
-// input rows that block touches, each loaded once and fed to the matrix cores
-// for every output row and tap it contributes to (the 16 -> 16 layers march
-// along z with kRY rows per wavefront).
+// Tiles of the first layer: a wavefront owns 16 cells along x of a block of
+// kRY x kRZ output rows (y, z) and walks the (kRY + 2) x (kRZ + 2) input rows
+// that block touches, each loaded once and fed to the matrix cores for every
+// output row and tap it contributes to (the other layers march along z with
+// kRY rows per wavefront).
 constexpr int kRY = 4, kRZ = 4;
 // input rows whose loads are in flight ahead of the products that use them
-// (for the first and last layers; 8 measured fastest of 2, 4, 6, 8)
+// (first layer; 8 measured fastest of 2, 4, 6, 8)
 constexpr int kAhead = 8;
 
 // The 16 -> 16 layers run on gfx950's K = 32 product
@@ -284,23 +284,27 @@ __global__ void __launch_bounds__(256, 2) k_conv16_zm(int n, int batch,
     }
 }
 
-// Last layer (16 inputs, 1 output): the kRY x kRZ = 16 output rows of the block
-// are the 16 matrix rows of the weight operand, so one product per input row
-// and x shift covers them all (108 products per tile instead of 432 with 15 of
-// 16 output channels idle).  For input row (iy, iz) at x shift dx = q - 1 the
-// weight operand is W'[n][ci] = W[ci][tap(dx, iy - 1 - oy, iz - 1 - oz)] for
-// output row n = oy + kRY oz, zero where the offset is out of reach.  The block
-// keeps W in LDS on a zero-padded (dz, dy) grid of [-4, 4]^2, so every lane
-// reads its operand at its own base plus a compile-time offset.  The other
-// operand is the input row, 4 channels of one cell per lane.
-// y = yscale * output, FP32.
+// The last layer's weights sit in LDS on a zero-padded (dz, dy) grid of [-4, 4]^2.
 constexpr int kPadW = 9;   // dy, dz in [-4, 4]
-__global__ void __launch_bounds__(256) k_conv16_final_rows(int n, int batch,
-                                                           const uint16_t* __restrict__ in,
-                                                           const v4s* __restrict__ wfin,
-                                                           float* __restrict__ yout, float yscale) {
-    static_assert(kRY * kRZ == 16, "output rows fill the 16 matrix columns");
-    static_assert(kRY <= 4 && kRZ <= 4, "padded grid covers every row offset");
+
+// The last layer as a z-march: a wavefront owns 16 cells along x times kRY
+// rows along y and walks ZC output planes.  The matrix columns (output rows of
+// the product, weights as the A operand) are the kRY rows of the three output
+// planes an input plane reaches, held in a ring: column 4 s + oy is row oy of
+// the output plane in slot s (s = plane mod 3; columns 12-15 idle).  Input
+// plane by input plane, each of its (kRY + 2) rows and 3 x shifts is one
+// product whose weight operand the lane takes from the padded (dz, dy) grid at
+// the offsets of its column; a column whose plane lies outside the chunk reads
+// the grid's zeros.  After an input plane the output plane of its dz = +1 taps
+// is complete: the lanes of its slot store it and clear their accumulators.
+// Each input row is loaded once per plane, into its register right after its
+// product (a plane of products covers the load).  y = yscale * output, FP32.
+template <int ZC>
+__global__ void __launch_bounds__(256) k_conv16_final_zm(int n, int batch,
+                                                         const uint16_t* __restrict__ in,
+                                                         const v4s* __restrict__ wfin,
+                                                         float* __restrict__ yout, float yscale) {
+    static_assert(kRY == 4, "three planes of kRY rows fit the 16 matrix columns");
     // wl[((dz + 4) kPadW + dy + 4) 3 + q][g]: channels 4g..4g+3 of tap (q - 1, dy, dz)
     __shared__ v4s wl[kPadW * kPadW * 3 * 4];
     for (int i = threadIdx.x; i < kPadW * kPadW * 3 * 4; i += blockDim.x) {
@@ -311,55 +315,65 @@ __global__ void __launch_bounds__(256) k_conv16_final_rows(int n, int batch,
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int segs = n / 16, nyb = n / kRY, nzb = n / kRZ;
-    const long nwaves = (long)batch * nzb * nyb * segs;
+    const int segs = n / 16, nyb = n / kRY, nzc = n / ZC;
+    const long nwaves = (long)batch * nzc * nyb * segs;
     if (wave >= nwaves) return;  // whole wavefront; no block barrier below
     const int iseg = (int)(wave % segs);
     long rest = wave / segs;
     const int j0 = (int)(rest % nyb) * kRY;
     rest /= nyb;
-    const int k0 = (int)(rest % nzb) * kRZ;
-    const int b = (int)(rest / nzb);
-    const size_t N = (size_t)n * n * n;
+    const int k0 = (int)(rest % nzc) * ZC;
+    const int b = (int)(rest / nzc);
+    const size_t N = (size_t)n * n * n, nn = (size_t)n * n;
     const int m = lane & 15, g = lane >> 4;
-    const int nn = lane & 15, oy = nn % kRY, oz = nn / kRY;
-    // entry of (iy, iz, q) for this lane: wbase + ((iz kPadW + iy) 3 + q) 4
-    const v4s* wbase = wl + (((3 - oz) * kPadW + (3 - oy)) * 3) * 4 + g;
+    const int col = lane & 15, oy = col % kRY, slot = col / kRY;   // this lane's A row (output column)
     const uint16_t* inb = in + (size_t)b * N * 16 + 4 * g;
-    int xo[3];
+    // this lane's element offset of input row iy, shift q within a plane
+    constexpr int kItemsF = (kRY + 2) * 3;
+    int off[kItemsF];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) xo[q] = wrapn(iseg * 16 + m + q - 1, n);
-    constexpr int kRW = kRY + 2, kRows = kRW * (kRZ + 2);
-    auto load_row = [&](int rrow, v4s (&a)[3]) {
-        const int iz = rrow / kRW, iy = rrow % kRW;
-        const size_t row = (size_t)n * ((size_t)wrapn(j0 - 1 + iy, n) + (size_t)n * wrapn(k0 - 1 + iz, n));
-#pragma clang loop unroll(full)
-        for (int q = 0; q < 3; ++q) a[q] = *reinterpret_cast<const v4s*>(inb + (row + xo[q]) * 16);
-    };
-    v4s abuf[kAhead + 1][3];
-#pragma clang loop unroll(full)
-    for (int r = 0; r < kAhead; ++r) load_row(r, abuf[r]);
-    v4f acc = {0.f, 0.f, 0.f, 0.f};
-#pragma clang loop unroll(full)
-    for (int rrow = 0; rrow < kRows; ++rrow) {
-        if (rrow + kAhead < kRows) load_row(rrow + kAhead, abuf[(rrow + kAhead) % (kAhead + 1)]);
-        __builtin_amdgcn_sched_barrier(0);
-        const int iz = rrow / kRW, iy = rrow % kRW;
-#pragma clang loop unroll(full)
-        for (int q = 0; q < 3; ++q)
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wbase[((iz * kPadW + iy) * 3 + q) * 4],
-                                                            abuf[rrow % (kAhead + 1)][q],
-                                                            acc, 0, 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
+    for (int it = 0; it < kItemsF; ++it) {
+        const int iy = it / 3, q = it % 3;
+        off[it] = (n * wrapn(j0 - 1 + iy, n) + wrapn(iseg * 16 + m + q - 1, n)) * 16;
     }
-    // computed as D^T (weights as the A operand): lane (g, m) holds cell m of
-    // output rows 4g + e, so each store covers 16 consecutive cells of 4 rows
+    auto plane_ptr = [&](int t) { return inb + nn * 16 * (size_t)wrapn(k0 - 1 + t, n); };
+    v4s a[kItemsF];
+    {
+        const uint16_t* pb = plane_ptr(0);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int row = 4 * g + e;
-        const size_t cell = (size_t)(iseg * 16 + m) +
-                            (size_t)n * ((size_t)(j0 + row % kRY) + (size_t)n * (k0 + row / kRY));
-        yout[(size_t)b * N + cell] = acc[e] * yscale;
+        for (int it = 0; it < kItemsF; ++it) a[it] = *reinterpret_cast<const v4s*>(pb + off[it]);
+    }
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < ZC + 2; ++t) {
+        const bool more = t + 1 < ZC + 2;
+        const uint16_t* pn = plane_ptr(more ? t + 1 : t);
+        // the output plane of this lane's slot at input plane t: the one of
+        // t - 2, t - 1, t congruent to the slot mod 3; its dz = t - 1 - oz, or
+        // the grid's zeros (dz = 4) when it is outside the chunk or the slot idle
+        const int oz = t - 2 + ((slot - (t - 2) % 3 + 3) % 3);
+        const int dz = slot < 3 && oz >= 0 && oz < ZC ? t - 1 - oz : 4;
+        const v4s* wb = wl + (((dz + 4) * kPadW + (3 - oy)) * 3) * 4 + g;
+#pragma unroll
+        for (int it = 0; it < kItemsF; ++it) {
+            const int iy = it / 3, q = it % 3;
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wb[(iy * 3 + q) * 4], a[it], acc, 0, 0, 0);
+            if (more) a[it] = *reinterpret_cast<const v4s*>(pn + off[it]);
+        }
+        // output plane t - 2 is complete: lane (g, m) holds rows 4 g + e of
+        // cell m, so the lanes of its slot store rows 0..3 and clear them
+        if (t >= 2) {
+            const int sd = (t - 2) % 3;
+            if (g == sd) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const size_t cell = (size_t)(iseg * 16 + m) +
+                                        (size_t)n * ((size_t)(j0 + e) + (size_t)n * (k0 + t - 2));
+                    yout[(size_t)b * N + cell] = acc[e] * yscale;
+                    acc[e] = 0.f;
+                }
+            }
+        }
     }
 }
 
@@ -526,7 +540,7 @@ __global__ void k_pack_rows4(const float* __restrict__ w, int cin, int cout, v4s
     wpk[t] = v;
 }
 
-// Pack the last layer (16 inputs, 1 output) for k_conv16_final_rows:
+// Pack the last layer (16 inputs, 1 output) for k_conv16_final_zm:
 // wfin[tap * 4 + g] = BF16 W[0][4g + e][tap], e = 0..3.
 __global__ void k_pack_final(const float* __restrict__ w, v4s* __restrict__ wfin) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -731,7 +745,7 @@ size_t net_weight_offset(int layer) {
 
 // Forward operands: layer 1 for k_conv (7 K-blocks), layers 2-4 (27 each),
 // layer 1 again for k_conv4_rows (9 K-blocks), layer 4 for
-// k_conv16_final_rows (27 taps x 4 channel groups), then layers 2 and 3 for
+// k_conv16_final_zm (27 taps x 4 channel groups), then layers 2 and 3 for
 // k_conv16_zm (30 K = 32 operands each).
 constexpr size_t kPackV4 = (size_t)(7 + 27 + 27 + 27 + 9) * 64 + 27 * 4;
 constexpr int kPairOps = 2 * kSlots * 3 * 64;
@@ -802,8 +816,12 @@ void net_forward(hipStream_t s, int n, int batch, const void* wpk, const uint16_
     };
     layer(a, pair_ops(wpk, 1), b);
     layer(b, pair_ops(wpk, 2), a);
-    hipLaunchKernelGGL(k_conv16_final_rows, GR, B, 0, s, n, batch, a,
-                       reinterpret_cast<const v4s*>(wpk) + (7 + 27 + 27 + 27 + 9) * 64, y, yscale);
+    const v4s* wfin = reinterpret_cast<const v4s*>(wpk) + (7 + 27 + 27 + 27 + 9) * 64;
+    switch (zc) {
+    case 16: hipLaunchKernelGGL(k_conv16_final_zm<16>, GZ, B, 0, s, n, batch, a, wfin, y, yscale); break;
+    case 8: hipLaunchKernelGGL(k_conv16_final_zm<8>, GZ, B, 0, s, n, batch, a, wfin, y, yscale); break;
+    default: hipLaunchKernelGGL(k_conv16_final_zm<4>, GZ, B, 0, s, n, batch, a, wfin, y, yscale); break;
+    }
 }
 
 // ---- training workspace ----
