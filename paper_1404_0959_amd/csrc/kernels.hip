@@ -2845,7 +2845,8 @@ __global__ void __launch_bounds__(kTX * kTY) k_tiled(Phys ph, DevState* st, K ke
     const size_t N = ncell(ph);
     K k = kern;
     k.member(ph, st + mem_);
-    if (k.skip(st + mem_)) return;   // whole block, before any barrier
+    if (MEMBER_FIRST()) k.lead(st + mem_);   // state a launch records even when it skips
+    if (k.skip(st + mem_)) return;           // whole block, before any barrier
     const int n = ph.n, cz = ph.cz;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kTX * ty;
     const int i0 = bp_.x * kTX, j0 = bp_.y * kTY;
@@ -3044,6 +3045,8 @@ struct TiledBase {
     __device__ void first(DevState*) const {}
     // true: the member has nothing to do in this launch (a solve already stopped)
     __device__ bool skip(const DevState*) const { return false; }
+    // the member's first thread, before the skip test
+    __device__ void lead(DevState*) const {}
 };
 
 template <typename T>
@@ -3455,6 +3458,142 @@ struct TiledCorrFluxUpdate : TiledBase<T> {
             const double sg = courant_rate(fp, fm, r, rref, V);
             acc[3] = sg > acc[3] ? sg : acc[3];
         }
+    }
+};
+
+// The Chebyshev-preconditioned CG's two launches, as k_cheb_res and
+// k_cheb_dir (the head of each, from the partial sums of the previous launch
+// of nb blocks, runs in member(); its state writes in lead()).
+template <typename T>
+struct TiledChebRes : TiledBase<T> {
+    static constexpr int NS = 4;          // r_{k-1}, q_{k-1}, diag, w
+    static constexpr int NR = 2;          // (r, z), (r, r)
+    const T* sf[4];
+    const T* p;
+    T *rout, *x, *z;
+    const DevState* st0;                  // member 0's state
+    const double *part_theta, *part_prev;
+    unsigned nb_theta, nb;
+    int k;
+    double c0, c1, alpha;
+    T inv_h2;
+    bool stopped;
+    struct Pts { T p, x; };
+    __device__ void member(const Phys& ph, const DevState* d) {
+        const int mem = (int)(d - st0);
+        inv_h2 = (T)ph.inv_h2;
+        stopped = k > d->pcg.it_stop;
+        alpha = 0.0;
+        if (k == 0) {
+            double t[1];
+            reduce_member<1, 1u>(part_theta, nb_theta, ph.batch, mem, t);
+            const double a = -t[0], b = 2.0 - a, mu = (b + a) / (b - a), t2 = 2.0 * mu * mu - 1.0;
+            c0 = 8.0 * mu / ((b - a) * t2);
+            c1 = -8.0 / ((b - a) * (b - a) * t2);
+        } else {
+            c0 = d->pcg.cheb[0];
+            c1 = d->pcg.cheb[1];
+            double t[kChebSet];
+            reduce_member<kChebSet, 0u>(part_prev, nb, ph.batch, mem, t);
+            alpha = t[kChebRes] / t[kChebDir];
+        }
+    }
+    __device__ void lead(DevState* d) const {
+        if (k == 0) {
+            d->pcg.cheb[0] = c0;
+            d->pcg.cheb[1] = c1;
+        }
+    }
+    __device__ bool skip(const DevState*) const { return stopped; }
+    __device__ void init(double* acc) const { acc[0] = acc[1] = 0.0; }
+    __device__ Pts load(size_t P) const { return {p[P], x[P]}; }
+    __device__ void cell(size_t P, const T (&v)[4][13], const T (&)[3], const T (&)[3],
+                         const Pts& pt, double* acc) const {
+        const T al = (T)alpha;
+        auto res = [&](int i) -> T { return k == 0 ? v[0][i] : v[0][i] - al * v[1][i]; };
+        auto tv = [&](int d, int sgn) -> T {
+            const int i = 1 + 4 * d + (sgn < 0 ? 1 : 2);   // g13 index of the +-1 neighbour
+            return res(i) / v[2][i];
+        };
+        const T rP = res(0), tP = rP / v[2][0];
+        T s = T(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) s += i4g(v[3], d, 0) * tv(d, 1) + i4g(v[3], d, -1) * tv(d, -1);
+        const T Mt = v[2][0] * tP - s * inv_h2;
+        const T zP = (T)c0 * tP + (T)c1 * Mt / v[2][0];
+        if (k > 0) {
+            x[P] = pt.x + al * pt.p;
+            rout[P] = rP;
+        }
+        z[P] = zP;
+        acc[0] += (double)rP * (double)zP;
+        acc[1] += (double)rP * (double)rP;
+    }
+};
+
+template <typename T>
+struct TiledChebDir : TiledBase<T> {
+    static constexpr int NS = 3;          // z_k, p_{k-1}, w
+    static constexpr int NR = 1;          // (p, q)
+    const T* sf[3];
+    const T* diag;
+    T *pout, *q;
+    const DevState* st0;
+    const double *part_u, *part_prev, *part_cur;
+    unsigned nb_u, nb;
+    int k, maxit;
+    double beta, bb, rr;
+    T inv_h2;
+    bool stopped, stop, conv;
+    struct Pts { T dg; };
+    __device__ void member(const Phys& ph, const DevState* d) {
+        const int mem = (int)(d - st0);
+        inv_h2 = (T)ph.inv_h2;
+        stopped = k > d->pcg.it_stop;
+        double t[kChebSet];
+        reduce_member<kChebSet, 0u>(part_cur, nb, ph.batch, mem, t);
+        if (k == 0) {
+            double u[3];
+            reduce_member<3, 0u>(part_u, nb_u, ph.batch, mem, u);
+            bb = u[2];
+        } else {
+            bb = d->pcg.bb;
+        }
+        rr = t[kChebRes + 1];
+        conv = rr <= d->pcg.tol2 * bb;
+        stop = conv || k >= maxit;
+        beta = 0.0;
+        if (k > 0 && !stop) {
+            double tp[kChebSet];
+            reduce_member<kChebSet, 0u>(part_prev, nb, ph.batch, mem, tp);
+            beta = t[kChebRes] / tp[kChebRes];
+        }
+    }
+    __device__ void lead(DevState* d) const {
+        if (stopped) return;
+        if (k == 0) d->pcg.bb = bb;
+        d->pcg.rr = rr;
+        d->pcg.iters = k;
+        if (stop) {
+            d->pcg.it_stop = k;
+            d->pcg.converged = conv ? 1 : 0;
+        }
+    }
+    __device__ bool skip(const DevState*) const { return stopped || stop; }
+    __device__ Pts load(size_t P) const { return {diag[P]}; }
+    __device__ void cell(size_t P, const T (&v)[3][13], const T (&)[3], const T (&)[3],
+                         const Pts& pt, double* acc) const {
+        const T be = (T)beta;
+        auto dir = [&](int i) -> T { return k == 0 ? v[0][i] : v[0][i] + be * v[1][i]; };
+        const T pP = dir(0);
+        T s = T(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            s += i4g(v[2], d, 0) * dir(1 + 4 * d + 2) + i4g(v[2], d, -1) * dir(1 + 4 * d + 1);
+        const T qP = pt.dg * pP - s * inv_h2;
+        pout[P] = pP;
+        q[P] = qP;
+        acc[0] += (double)pP * (double)qP;
     }
 };
 
@@ -3954,17 +4093,58 @@ void Ops<T>::cheb_theta(const Launch& L, hipStream_t s, const Phys& ph, const T*
     LAUNCH(k_cheb_theta<T>, L, s, ph, psidt, diag, part);
 }
 template <typename T>
-void Ops<T>::cheb_res(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int k,
-                      const T* rin, T* rout, const T* q, const T* p, const T* diag, const T* w, T* x,
-                      T* z, const double* part_theta, unsigned nb_theta, const double* part_prev,
-                      double* part_out) {
+void Ops<T>::cheb_res(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph, DevState* st,
+                      int k, const T* rin, T* rout, const T* q, const T* p, const T* diag, const T* w,
+                      T* x, T* z, const double* part_theta, unsigned nb_theta,
+                      const double* part_prev, double* part_out) {
+    if (TL.nblocks) {
+        TiledChebRes<T> kr{};
+        kr.sf[0] = rin;
+        kr.sf[1] = k == 0 ? rin : q;   // q_{k-1} is not read at k = 0
+        kr.sf[2] = diag;
+        kr.sf[3] = w;
+        kr.p = p;
+        kr.rout = rout;
+        kr.x = x;
+        kr.z = z;
+        kr.st0 = st;
+        kr.part_theta = part_theta;
+        kr.nb_theta = nb_theta;
+        kr.part_prev = part_prev;
+        kr.nb = TL.nblocks;
+        kr.k = k;
+        kr.part = part_out + kChebRes * (size_t)TL.nblocks;
+        tiled_launch<T>(TL, s, ph, st, kr);
+        return;
+    }
     LAUNCH(k_cheb_res<T>, L, s, ph, st, k, rin, rout, q, p, diag, w, x, z, part_theta, nb_theta,
            part_prev, part_out);
 }
 template <typename T>
-void Ops<T>::cheb_dir(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int k, const T* z,
-                      const T* pin, T* pout, T* q, const T* diag, const T* w, const double* part_u,
-                      unsigned nb_u, const double* part_prev, double* part_cur, int maxit) {
+void Ops<T>::cheb_dir(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph, DevState* st,
+                      int k, const T* z, const T* pin, T* pout, T* q, const T* diag, const T* w,
+                      const double* part_u, unsigned nb_u, const double* part_prev,
+                      double* part_cur, int maxit) {
+    if (TL.nblocks) {
+        TiledChebDir<T> kd{};
+        kd.sf[0] = z;
+        kd.sf[1] = k == 0 ? z : pin;   // p_{k-1} is not read at k = 0
+        kd.sf[2] = w;
+        kd.diag = diag;
+        kd.pout = pout;
+        kd.q = q;
+        kd.st0 = st;
+        kd.part_u = part_u;
+        kd.nb_u = nb_u;
+        kd.part_prev = part_prev;
+        kd.part_cur = part_cur;
+        kd.nb = TL.nblocks;
+        kd.k = k;
+        kd.maxit = maxit;
+        kd.part = part_cur + kChebDir * (size_t)TL.nblocks;
+        tiled_launch<T>(TL, s, ph, st, kd);
+        return;
+    }
     LAUNCH(k_cheb_dir<T>, L, s, ph, st, k, z, pin, pout, q, diag, w, part_u, nb_u, part_prev, part_cur,
            maxit);
 }

@@ -186,14 +186,14 @@ struct Ops {
     // the direction/operator launches
     static void cheb_theta(const Launch& L, hipStream_t s, const Phys& ph, const T* psidt,
                            const T* diag, double* part);
-    static void cheb_res(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int k,
-                         const T* rin, T* rout, const T* q, const T* p, const T* diag, const T* w,
-                         T* x, T* z, const double* part_theta, unsigned nb_theta,
-                         const double* part_prev, double* part_out);
-    static void cheb_dir(const Launch& L, hipStream_t s, const Phys& ph, DevState* st, int k,
-                         const T* z, const T* pin, T* pout, T* q, const T* diag, const T* w,
-                         const double* part_u, unsigned nb_u, const double* part_prev,
-                         double* part_cur, int maxit);
+    static void cheb_res(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                         DevState* st, int k, const T* rin, T* rout, const T* q, const T* p,
+                         const T* diag, const T* w, T* x, T* z, const double* part_theta,
+                         unsigned nb_theta, const double* part_prev, double* part_out);
+    static void cheb_dir(const Launch& L, const Launch& TL, hipStream_t s, const Phys& ph,
+                         DevState* st, int k, const T* z, const T* pin, T* pout, T* q,
+                         const T* diag, const T* w, const double* part_u, unsigned nb_u,
+                         const double* part_prev, double* part_cur, int maxit);
     static void helm_start(const Launch& L, hipStream_t s, const Phys& ph, DevState* st,
                            const T* psidt, const T* w, const T* b, const T* x, T* r, T* diag,
                            double* part_u);

@@ -2608,10 +2608,10 @@ static pisoc_status run_cheb(pisoc_ctx* ctx, const double* psidt, const double* 
             double* prev = ctx->part(PS_CG + kChebSet * ((kk + 1) & 1));
             double* rin = r[kk == 0 ? 0 : (kk - 1) & 1];
             double* pin = p[(kk + 1) & 1];
-            O::cheb_res(L, s, ctx->ph, ctx->st, kk, rin, r[kk & 1], q, pin, diag, w, x, z, theta, nb,
-                        prev, cur);
-            O::cheb_dir(L, s, ctx->ph, ctx->st, kk, z, pin, p[kk & 1], q, diag, w, ctx->part(PS_U), nb,
-                        prev, cur, maxit);
+            O::cheb_res(L, ctx->TL, s, ctx->ph, ctx->st, kk, rin, r[kk & 1], q, pin, diag, w, x, z,
+                        theta, nb, prev, cur);
+            O::cheb_dir(L, ctx->TL, s, ctx->ph, ctx->st, kk, z, pin, p[kk & 1], q, diag, w,
+                        ctx->part(PS_U), nb, prev, cur, maxit);
         }
         pisoc_status st = sync_state(ctx);
         if (st != PISOC_OK) return st;
