@@ -125,15 +125,9 @@ __global__ void __launch_bounds__(256) k_conv(int n, int batch, const uint16_t* 
     }
 }
 
-// Tiles of the first layer: a wavefront owns 16 cells along x of a block of
-// kRY x kRZ output rows (y, z) and walks the (kRY + 2) x (kRZ + 2) input rows
-// that block touches, each loaded once and fed to the matrix cores for every
-// output row and tap it contributes to (the other layers march along z with
-// kRY rows per wavefront).
-constexpr int kRY = 4, kRZ = 4;
-// input rows whose loads are in flight ahead of the products that use them
-// (first layer; 8 measured fastest of 2, 4, 6, 8)
-constexpr int kAhead = 8;
+// Every layer marches along z: a wavefront owns 16 cells along x times kRY
+// rows along y and walks a chunk of output planes.
+constexpr int kRY = 4;
 
 // The 16 -> 16 layers run on gfx950's K = 32 product
 // (v_mfma_f32_16x16x32_bf16, twice the work of the K = 16 form per issue).
@@ -147,29 +141,6 @@ constexpr int kAhead = 8;
 // the ends of odd and even runs.
 constexpr int kItems = 3 * (kRY + 2), kPairs = kItems / 2, kSlots = 5;
 static_assert(kItems % 2 == 0, "items pair up within a plane");
-
-// Output of a tile computed as D^T (weights as the A operand): lane (g, m)
-// holds channels 4g..4g+3 of cell x of each output row, stored as one 8-byte
-// BF16 quad (ReLU when relu is set).
-__device__ inline void store_rows(const v4f (&acc)[kRY][kRZ], uint16_t* __restrict__ out, int n,
-                                  int x, int j0, int k0, int g, int relu) {
-#pragma unroll
-    for (int oz = 0; oz < kRZ; ++oz)
-#pragma unroll
-        for (int oy = 0; oy < kRY; ++oy) {
-            const size_t cell = (size_t)x + (size_t)n * ((size_t)(j0 + oy) + (size_t)n * (k0 + oz));
-            float v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float a = acc[oy][oz][e];
-                v[e] = relu && !(a > 0.f) ? 0.f : a;
-            }
-            uint2 q;
-            q.x = bf16x2(v[0], v[1]);
-            q.y = bf16x2(v[2], v[3]);
-            *reinterpret_cast<uint2*>(out + cell * 16 + 4 * g) = q;
-        }
-}
 
 __device__ inline v4f mfma_k32(v8s a, v8s b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
@@ -188,7 +159,7 @@ __device__ inline v4f mfma_k32(v8s a, v8s b, v4f c) {
 // full (ZC a template parameter), so that every ring slot and edge test is a
 // constant and the loads stay in flight across planes (with run-time tests the
 // compiler drained them at every branch: 1.65 against 1.12 ms for the
-// network at 256^3).  Against one wavefront per 16 x kRY x kRZ tile, which
+// network at 256^3).  Against one wavefront per 16 x 4 x 4 tile, which
 // reread 6 input planes per 4 output planes and reloaded the weights per
 // tile, the layer takes about 290 instead of 480 us at 256^3.
 __device__ inline void store_plane_rows(const v4f (&acc)[kRY], uint16_t* __restrict__ out, int n,
@@ -377,72 +348,82 @@ __global__ void __launch_bounds__(256) k_conv16_final_zm(int n, int batch,
     }
 }
 
-// First layer (2 input channels, channel-last BF16 [cell][4] input) with input
-// reuse across output rows: a K-block covers one input-row offset (dy, dz),
-// lane group g holding the cell shifted by dx = g - 1 (group 3 idle), so each
-// input row is one 8-byte load per lane feeding every output row it touches:
-// 144 products per 36 loads for 16 cells x kRY x kRZ rows.  ReLU, BF16 out.
-__global__ void __launch_bounds__(256) k_conv4_rows(int n, int batch, const uint16_t* __restrict__ in,
-                                                    const v4s* __restrict__ wpk,
-                                                    uint16_t* __restrict__ out) {
+// The first layer (2 input channels, channel-last BF16 [cell][4] input) as a
+// z-march like the 16 -> 16 layers.  One K = 16 block per input-row offset
+// (dy, dz): lane group g holds the 4 channels of the cell shifted by
+// dx = g - 1 (group 3 meets zero weights), so an input row is one 8-byte load
+// per lane and the 9 weight operands stay in registers.  A wavefront owns 16
+// cells along x times kRY rows along y and walks ZC output planes; each input
+// plane's kRY + 2 rows, loaded into their registers right after their last
+// product, feed the output rows of the three output planes in reach, held in
+// a ring of accumulators.  ReLU, BF16 out.  Against one wavefront per
+// 16 x 4 x 4 tile of output rows (36 input rows per 16 output rows) the
+// network takes 1.04 instead of 1.07 ms at 256^3.
+template <int ZC>
+__global__ void __launch_bounds__(256) k_conv4_zm(int n, int batch, const uint16_t* __restrict__ in,
+                                                  const v4s* __restrict__ wpk,
+                                                  uint16_t* __restrict__ out) {
     const int lane = threadIdx.x & 63;
     const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int segs = n / 16, nyb = n / kRY, nzb = n / kRZ;
-    const long nwaves = (long)batch * nzb * nyb * segs;
+    const int segs = n / 16, nyb = n / kRY, nzc = n / ZC;
+    const long nwaves = (long)batch * nzc * nyb * segs;
     if (wave >= nwaves) return;  // whole wavefront; no block barrier below
     const int iseg = (int)(wave % segs);
     long rest = wave / segs;
     const int j0 = (int)(rest % nyb) * kRY;
     rest /= nyb;
-    const int k0 = (int)(rest % nzb) * kRZ;
-    const int b = (int)(rest / nzb);
-    const size_t N = (size_t)n * n * n;
+    const int k0 = (int)(rest % nzc) * ZC;
+    const int b = (int)(rest / nzc);
+    const size_t N = (size_t)n * n * n, nn = (size_t)n * n;
     const int m = lane & 15, g = lane >> 4;
     v4s B[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) B[t] = wpk[t * 64 + lane];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) asm volatile("" : "+v"(B[t]));
-    v4f acc[kRY][kRZ];
-#pragma unroll
-    for (int oy = 0; oy < kRY; ++oy)
-#pragma unroll
-        for (int oz = 0; oz < kRZ; ++oz) acc[oy][oz] = v4f{0.f, 0.f, 0.f, 0.f};
+    constexpr int kRW = kRY + 2;
     const uint16_t* inb = in + (size_t)b * N * 4;
     const int xo = wrapn(iseg * 16 + m + (g < 3 ? g - 1 : 0), n);   // group 3: weights are zero
-    constexpr int kRW = kRY + 2, kRows = kRW * (kRZ + 2);
-    auto load_row = [&](int iz, int iy) {
-        const size_t row = (size_t)n * ((size_t)wrapn(j0 - 1 + iy, n) + (size_t)n * wrapn(k0 - 1 + iz, n));
-        return *reinterpret_cast<const v4s*>(inb + (row + xo) * 4);
-    };
-    v4s abuf[kAhead + 1];
-#pragma clang loop unroll(full)
-    for (int r = 0; r < kAhead; ++r) abuf[r] = load_row(r / kRW, r % kRW);
-#pragma clang loop unroll(full)
-    for (int iz = 0; iz < kRZ + 2; ++iz) {
-#pragma clang loop unroll(full)
+    int off[kRW];
+#pragma unroll
+    for (int iy = 0; iy < kRW; ++iy) off[iy] = (n * wrapn(j0 - 1 + iy, n) + xo) * 4;
+    auto plane_ptr = [&](int t) { return inb + nn * 4 * (size_t)wrapn(k0 - 1 + t, n); };
+    v4s a[kRW];
+    {
+        const uint16_t* pb = plane_ptr(0);
+#pragma unroll
+        for (int iy = 0; iy < kRW; ++iy) a[iy] = *reinterpret_cast<const v4s*>(pb + off[iy]);
+    }
+    v4f acc[3][kRY];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int oy = 0; oy < kRY; ++oy) acc[r][oy] = v4f{0.f, 0.f, 0.f, 0.f};
+    uint16_t* outb = out + (size_t)b * N * 16;
+#pragma unroll
+    for (int t = 0; t < ZC + 2; ++t) {
+        const bool more = t + 1 < ZC + 2;
+        const uint16_t* pn = plane_ptr(more ? t + 1 : t);
+#pragma unroll
         for (int iy = 0; iy < kRW; ++iy) {
-            const int rrow = iz * kRW + iy;
-            if (rrow + kAhead < kRows)
-                abuf[(rrow + kAhead) % (kAhead + 1)] = load_row((rrow + kAhead) / kRW, (rrow + kAhead) % kRW);
-            __builtin_amdgcn_sched_barrier(0);
-            const v4s a = abuf[rrow % (kAhead + 1)];
-#pragma clang loop unroll(full)
-            for (int oz = 0; oz < kRZ; ++oz) {
-                const int dz = iz - 1 - oz;
-                if (dz < -1 || dz > 1) continue;
-#pragma clang loop unroll(full)
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int oz = t - 1 - dz;   // ring slot oz mod 3
+                if (oz < 0 || oz >= ZC) continue;
+#pragma unroll
                 for (int oy = 0; oy < kRY; ++oy) {
                     const int dy = iy - 1 - oy;
                     if (dy < -1 || dy > 1) continue;
-                    acc[oy][oz] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(B[(dz + 1) * 3 + dy + 1], a,
-                                                                            acc[oy][oz], 0, 0, 0);
+                    acc[oz % 3][oy] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                        B[(dz + 1) * 3 + dy + 1], a[iy], acc[oz % 3][oy], 0, 0, 0);
                 }
             }
-            __builtin_amdgcn_sched_barrier(0);
+            if (more) a[iy] = *reinterpret_cast<const v4s*>(pn + off[iy]);
+        }
+        if (t >= 2) {   // output plane t - 2 has had its last input plane
+            store_plane_rows(acc[(t - 2) % 3], outb, n, iseg * 16 + m, j0, k0 + t - 2, g, 1);
+#pragma unroll
+            for (int oy = 0; oy < kRY; ++oy) acc[(t - 2) % 3][oy] = v4f{0.f, 0.f, 0.f, 0.f};
         }
     }
-    store_rows(acc, out + (size_t)b * N * 16, n, iseg * 16 + m, j0, k0, g, 1);
 }
 
 // Weight gradient of one layer: partial sums over this wavefront's cells of
@@ -521,7 +502,7 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int nwaves, int c
 }
 
 // Pack the first layer (cin input channels, cout <= 16 outputs) for
-// k_conv4_rows: one K-block per input-row offset (dy, dz), t9 = (dz+1) 3 + (dy+1);
+// k_conv4_zm: one K-block per input-row offset (dy, dz), t9 = (dz+1) 3 + (dy+1);
 // its K entry 4 g + c holds channel c of the cell dx = g - 1 along x (g < 3;
 // g = 3 and c >= cin are zero).
 __global__ void k_pack_rows4(const float* __restrict__ w, int cin, int cout, v4s* __restrict__ wpk) {
@@ -744,7 +725,7 @@ size_t net_weight_offset(int layer) {
 }
 
 // Forward operands: layer 1 for k_conv (7 K-blocks), layers 2-4 (27 each),
-// layer 1 again for k_conv4_rows (9 K-blocks), layer 4 for
+// layer 1 again for k_conv4_zm (9 K-blocks), layer 4 for
 // k_conv16_final_zm (27 taps x 4 channel groups), then layers 2 and 3 for
 // k_conv16_zm (30 K = 32 operands each).
 constexpr size_t kPackV4 = (size_t)(7 + 27 + 27 + 27 + 9) * 64 + 27 * 4;
@@ -780,12 +761,6 @@ static dim3 conv_grid(int n, int batch) {
     return dim3((unsigned)((waves + 3) / 4));
 }
 
-// Blocks of 4 wavefronts, one wavefront per 16 cells x kRY x kRZ output rows.
-static dim3 conv_rows_grid(int n, int batch) {
-    const long waves = (long)batch * (n / kRZ) * (n / kRY) * (n / 16);
-    return dim3((unsigned)((waves + 3) / 4));
-}
-
 // Output planes per wavefront of k_conv16_zm: the longest chunk (16, 8 or 4
 // planes, dividing n) that still gives at least 4096 wavefronts (32 planes
 // would spill registers).
@@ -803,10 +778,15 @@ static unsigned zm_blocks(int n, int batch, int zc) {
 void net_forward(hipStream_t s, int n, int batch, const void* wpk, const uint16_t* x4,
                  uint16_t* a, uint16_t* b, float* y, float yscale) {
     const v4s* p = reinterpret_cast<const v4s*>(wpk);
-    const dim3 GR = conv_rows_grid(n, batch), B(256);
-    hipLaunchKernelGGL(k_conv4_rows, GR, B, 0, s, n, batch, x4, p + (7 + 27 + 27 + 27) * 64, a);
+    const dim3 B(256);
     const int zc = zm_chunk(n, batch);
     const dim3 GZ(zm_blocks(n, batch, zc));
+    const v4s* w1 = p + (7 + 27 + 27 + 27) * 64;
+    switch (zc) {
+    case 16: hipLaunchKernelGGL(k_conv4_zm<16>, GZ, B, 0, s, n, batch, x4, w1, a); break;
+    case 8: hipLaunchKernelGGL(k_conv4_zm<8>, GZ, B, 0, s, n, batch, x4, w1, a); break;
+    default: hipLaunchKernelGGL(k_conv4_zm<4>, GZ, B, 0, s, n, batch, x4, w1, a); break;
+    }
     auto layer = [&](const uint16_t* src, const v8s* w, uint16_t* dst) {
         switch (zc) {
         case 16: hipLaunchKernelGGL(k_conv16_zm<16>, GZ, B, 0, s, n, batch, src, w, 1, dst); break;
