@@ -10,8 +10,9 @@ and velocity correction and dust transport.
 
 Prints one JSON line: cell-steps/s, the roofline figures of the dominant
 kernel (HIP events around every launch in the timed region, algorithmic bytes
-per launch counted by the library) and the FP64 CPU oracle timed on a bounded
-sample of the same workload on the host cores.
+per launch counted by the library), beside them the practical ceiling of the
+same read/write mixes measured by the library's streaming probe, and the FP64
+CPU oracle timed on a bounded sample of the same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -334,6 +335,35 @@ def measured_traffic(kernel, dtype, n):
     return sum((r["fetch_bytes"] + r["write_bytes"]) * r["launches"] for r in recs) / launches
 
 
+STREAM_MIXES = ((1, 1), (3, 2), (5, 3), (7, 4))
+
+
+def stream_ceiling(P, torch, n, reps=20):
+    """Practical HBM ceiling of the read/write mixes of the CG launches: the
+    library's plain streaming probe over n^3 FP32 fields, GB/s per mix (reads +
+    writes), timed with HIP events on the stream it runs on.  The CG moves
+    3 reads + 2 writes per cell at k = 0, 5 + 3 at odd k, 7 + 4 at even k."""
+    count = n ** 3 // 4 * 4
+    bufs = [torch.ones(count, dtype=torch.float32, device="cuda") for _ in range(11)]
+    out = {}
+    for r, w in STREAM_MIXES:
+        ins, outs = bufs[:r], bufs[7:7 + w]
+        for _ in range(3):
+            P.stream_probe(ins, outs)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            P.stream_probe(ins, outs)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3 / reps
+        out[f"{r}r{w}w"] = round(4.0 * count * (r + w) / sec / 1e9, 1)
+    del bufs
+    torch.cuda.empty_cache()
+    return out
+
+
 def roofline(prof):
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
     avg_ms = dom["ms"] / dom["launches"]
@@ -401,6 +431,14 @@ def main():
     roof, kernels = roofline(H["prof"])
     roof["traffic"] = measured_traffic(roof["kernel"], "f64" if head == "fp64" else "f32+f64",
                                        args.n)
+    gbs = stream_ceiling(P, torch, args.n)
+    # odd and even CG iterations alternate: 8 and 11 words per cell, bytes-weighted
+    mix = 19.0 / (8.0 / gbs["5r3w"] + 11.0 / gbs["7r4w"])
+    roof["ceiling"] = {"kind": "streaming probe (k_stream), same read/write mixes, n^3 FP32 fields",
+                       "gbs": gbs, "cg_mix_gbs": round(mix, 1),
+                       "frac": round(roof["achieved"] / mix, 4)
+                       if roof["kernel"] == "k_pcg_spmv" else None}
+    log(f"streaming ceiling: {gbs}; CG mix {mix:.1f} GB/s")
     log(json.dumps(kernels))
 
     ens = None

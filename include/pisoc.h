@@ -509,6 +509,23 @@ pisoc_status pisoc_diag_qcrit(int32_t n, const double* d_u, double* d_q, double*
 pisoc_status pisoc_diag_sgs(int32_t n, const double* d_u, double* h_out, void* d_ws,
                             size_t ws_bytes, void* hip_stream);
 
+/* ---- measurement ------------------------------------------------------------
+ * Not in the paper: the practical HBM ceiling of a mix of reads and writes,
+ * against which the step's memory-bound kernels are read.  A plain streaming
+ * kernel computes out_w[i] = (w + 1) * (in_0[i] + ... + in_{reads-1}[i]) in
+ * FP32 for w < writes and i < count, walking the arrays in 16-byte vectors
+ * with a grid stride and non-temporal loads and stores, in `blocks` blocks of
+ * 256 threads (0: 16384).  h_in[reads], h_out[writes]: host arrays of device
+ * pointers, each 16-byte aligned, count floats each; outputs must not
+ * overlap inputs.  1 <= reads <= 8, 1 <= writes <= 4, count a multiple of 4.
+ * count 0 does nothing (the pointers are not read).  Asynchronous on
+ * hip_stream.  Errors: PISOC_ERR_INVALID (before any GPU work) for arguments
+ * outside these ranges or a NULL or misaligned pointer; PISOC_ERR_HIP when
+ * the launch fails. */
+pisoc_status pisoc_stream_probe(int32_t reads, int32_t writes, int64_t count,
+                                const float* const* h_in, float* const* h_out, int32_t blocks,
+                                void* hip_stream);
+
 /* ---- learned initial guess of the pressure correction --------------------
  * Not in the paper: a small network predicts the start of each pressure solve
  * from the corrector's Jacobi-scaled continuity defect and the pressure of the

@@ -301,21 +301,38 @@ __device__ inline double wave_reduce(double v) {
     return v;
 }
 
+// wave_reduce of NV values at once: each step's shuffles of all components
+// are issued together (one LDS round trip per step rather than one per step
+// and component), each component combined in wave_reduce's order.
+template <int NV, unsigned MAXMASK>
+__device__ inline void wave_reduce_all(double (&v)[NV]) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        double t[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) t[c] = __shfl_down(v[c], off, 64);
+#pragma unroll
+        for (int c = 0; c < NV; ++c)
+            v[c] = ((MAXMASK >> c) & 1u) ? combine<true>(v[c], t[c]) : combine<false>(v[c], t[c]);
+    }
+}
+
 // Block reduction of NV values over the block's waves (up to 16 waves of 64);
 // component c uses max when bit c of MAXMASK is set, else a sum.  Result valid
 // in thread 0.  The order of operations is fixed, so the result is bitwise
-// reproducible.
-template <int NV, unsigned MAXMASK>
+// reproducible.  LDS_ONLY: the barriers order only LDS accesses (lds_barrier),
+// so global loads and stores in flight stay in flight across the reduction.
+template <int NV, unsigned MAXMASK, bool LDS_ONLY = false>
 __device__ inline void block_reduce(double (&v)[NV], double* lds) {
     const int tid = flat_tid();
     const int lane = tid & 63, wave = tid >> 6;
     const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+    wave_reduce_all<NV, MAXMASK>(v);
+    if (lane == 0)
 #pragma unroll
-    for (int c = 0; c < NV; ++c) {
-        double x = ((MAXMASK >> c) & 1u) ? wave_reduce<true>(v[c]) : wave_reduce<false>(v[c]);
-        if (lane == 0) lds[wave * NV + c] = x;
-    }
-    __syncthreads();
+        for (int c = 0; c < NV; ++c) lds[wave * NV + c] = v[c];
+    if (LDS_ONLY) lds_barrier();
+    else __syncthreads();
     if (tid == 0) {
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
@@ -325,16 +342,17 @@ __device__ inline void block_reduce(double (&v)[NV], double* lds) {
             v[c] = acc;
         }
     }
-    __syncthreads();
+    if (LDS_ONLY) lds_barrier();
+    else __syncthreads();
 }
 
 // Per-block partials of a grid-wide reduction: thread 0 writes the block's
 // totals to part[c * num_blocks + block].  No fence is needed: the partials
 // are consumed by a later kernel on the same stream.
-template <int NV, unsigned MAXMASK>
+template <int NV, unsigned MAXMASK, bool LDS_ONLY = false>
 __device__ inline void block_partials(double (&v)[NV], double* part) {
     __shared__ double lds[16 * NV];
-    block_reduce<NV, MAXMASK>(v, lds);
+    block_reduce<NV, MAXMASK, LDS_ONLY>(v, lds);
     if (flat_tid() == 0) {
         const unsigned nb = num_blocks(), bid = flat_bid();
 #pragma unroll
@@ -343,7 +361,7 @@ __device__ inline void block_partials(double (&v)[NV], double* part) {
 }
 
 // Totals of count partials per column starting at `first`, columns nbt apart.
-template <int NV, unsigned MAXMASK>
+template <int NV, unsigned MAXMASK, bool LDS_ONLY = false>
 __device__ inline void reduce_partials_strided(const double* __restrict__ part, size_t nbt,
                                                size_t first, unsigned nb, double (&out)[NV]) {
     __shared__ double lds[16 * NV];
@@ -360,11 +378,12 @@ __device__ inline void reduce_partials_strided(const double* __restrict__ part, 
         }
         out[c] = acc;
     }
-    block_reduce<NV, MAXMASK>(out, lds);
+    block_reduce<NV, MAXMASK, LDS_ONLY>(out, lds);
     if (tid == 0)
 #pragma unroll
         for (int c = 0; c < NV; ++c) tot[c] = out[c];
-    __syncthreads();
+    if (LDS_ONLY) lds_barrier();
+    else __syncthreads();
 #pragma unroll
     for (int c = 0; c < NV; ++c) out[c] = tot[c];
 }
@@ -372,12 +391,12 @@ __device__ inline void reduce_partials_strided(const double* __restrict__ part, 
 // Totals of one member's partials: an earlier kernel with nbt blocks in all
 // wrote column c of block b at part[c nbt + b]; member m owns the blocks
 // [m nbt/batch, (m+1) nbt/batch).
-template <int NV, unsigned MAXMASK>
+template <int NV, unsigned MAXMASK, bool LDS_ONLY = false>
 __device__ inline void reduce_member(const double* __restrict__ part, unsigned nbt, int batch,
                                      int m, double (&out)[NV]) {
     const unsigned per = nbt / (unsigned)batch;
     double tmp[NV];
-    reduce_partials_strided<NV, MAXMASK>(part, nbt, (size_t)m * per, per, tmp);
+    reduce_partials_strided<NV, MAXMASK, LDS_ONLY>(part, nbt, (size_t)m * per, per, tmp);
 #pragma unroll
     for (int c = 0; c < NV; ++c) out[c] = tmp[c];
 }

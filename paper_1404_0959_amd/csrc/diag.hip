@@ -14,6 +14,9 @@
 // <|u|^2>/2.  Taylor micro-scale lambda = sqrt(5 sum E / D) with D = sum_k
 // |k|^2 |u_hat(k)|^2 / 2.  Every sum runs in a fixed order (bitwise
 // reproducible): per row of wavevectors, per plane, then over the planes.
+//
+// Also here: the plain streaming kernel that measures the practical HBM
+// ceiling of a given mix of reads and writes (no stencil, no reduction).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -346,6 +349,38 @@ DiagLayout diag_layout(int n) {
     return d;
 }
 
+// Streaming probe: out_w[i] = (w + 1) * (in_0[i] + ... + in_{R-1}[i]) over
+// 16-byte vectors, a flat grid walking the arrays with a grid stride,
+// non-temporal loads and stores (as the step's kernels stream their fields).
+constexpr int kStreamThreads = 256, kStreamBlocks = 16384;
+typedef float f4v __attribute__((ext_vector_type(4)));
+struct StreamPtrs {
+    const f4v* in[8];
+    f4v* out[4];
+};
+
+template <int R, int W>
+__global__ void __launch_bounds__(kStreamThreads) k_stream(StreamPtrs p, size_t n4) {
+    const size_t stride = (size_t)gridDim.x * kStreamThreads;
+    for (size_t i = (size_t)blockIdx.x * kStreamThreads + threadIdx.x; i < n4; i += stride) {
+        f4v a = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < R; ++r) a += __builtin_nontemporal_load(p.in[r] + i);
+#pragma unroll
+        for (int w = 0; w < W; ++w) __builtin_nontemporal_store(a * (float)(w + 1), p.out[w] + i);
+    }
+}
+
+template <int R>
+void launch_stream(int writes, dim3 g, hipStream_t s, const StreamPtrs& p, size_t n4) {
+    switch (writes) {
+    case 1: hipLaunchKernelGGL((k_stream<R, 1>), g, dim3(kStreamThreads), 0, s, p, n4); break;
+    case 2: hipLaunchKernelGGL((k_stream<R, 2>), g, dim3(kStreamThreads), 0, s, p, n4); break;
+    case 3: hipLaunchKernelGGL((k_stream<R, 3>), g, dim3(kStreamThreads), 0, s, p, n4); break;
+    default: hipLaunchKernelGGL((k_stream<R, 4>), g, dim3(kStreamThreads), 0, s, p, n4); break;
+    }
+}
+
 }  // namespace
 }  // namespace pisoc
 
@@ -464,6 +499,39 @@ pisoc_status pisoc_diag_sgs(int32_t n, const double* d_u, double* h_out, void* d
     if (hipMemcpy(t, out, sizeof(t), hipMemcpyDeviceToHost) != hipSuccess) return PISOC_ERR_HIP;
     for (int c = 0; c < 4; ++c) h_out[c] = t[c] / (double)N;
     return PISOC_OK;
+}
+
+pisoc_status pisoc_stream_probe(int32_t reads, int32_t writes, int64_t count,
+                                const float* const* h_in, float* const* h_out, int32_t blocks,
+                                void* hip_stream) {
+    if (reads < 1 || reads > 8 || writes < 1 || writes > 4 || count < 0 || count % 4 != 0 ||
+        blocks < 0)
+        return PISOC_ERR_INVALID;
+    if (count == 0) return PISOC_OK;
+    if (!h_in || !h_out) return PISOC_ERR_INVALID;
+    StreamPtrs p{};
+    for (int r = 0; r < reads; ++r) {
+        if (!h_in[r] || reinterpret_cast<uintptr_t>(h_in[r]) % 16 != 0) return PISOC_ERR_INVALID;
+        p.in[r] = reinterpret_cast<const f4v*>(h_in[r]);
+    }
+    for (int w = 0; w < writes; ++w) {
+        if (!h_out[w] || reinterpret_cast<uintptr_t>(h_out[w]) % 16 != 0) return PISOC_ERR_INVALID;
+        p.out[w] = reinterpret_cast<f4v*>(h_out[w]);
+    }
+    const size_t n4 = (size_t)count / 4;
+    const dim3 g((unsigned)(blocks > 0 ? blocks : kStreamBlocks));
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    switch (reads) {
+    case 1: launch_stream<1>(writes, g, s, p, n4); break;
+    case 2: launch_stream<2>(writes, g, s, p, n4); break;
+    case 3: launch_stream<3>(writes, g, s, p, n4); break;
+    case 4: launch_stream<4>(writes, g, s, p, n4); break;
+    case 5: launch_stream<5>(writes, g, s, p, n4); break;
+    case 6: launch_stream<6>(writes, g, s, p, n4); break;
+    case 7: launch_stream<7>(writes, g, s, p, n4); break;
+    default: launch_stream<8>(writes, g, s, p, n4); break;
+    }
+    return hipGetLastError() == hipSuccess ? PISOC_OK : PISOC_ERR_HIP;
 }
 
 }  // extern "C"

@@ -1030,12 +1030,12 @@ __device__ inline CgHead cg_head(const Phys& ph, PcgState& g, bool recorder, int
     double bb;
     if (k == 0) {
         double t[3];
-        reduce_member<3, 0u>(part_in, nb_in, ph.batch, mem, t);
+        reduce_member<3, 0u, true>(part_in, nb_in, ph.batch, mem, t);
         h.rr = t[1];
         bb = newb ? t[2] : g.bb;
     } else {
         double t[CG_COLS];
-        reduce_member<CG_COLS, 0u>(part_in, nb_in, ph.batch, mem, t);
+        reduce_member<CG_COLS, 0u, true>(part_in, nb_in, ph.batch, mem, t);
         const double a = t[CG_RZ] / t[CG_PQ];
         const double rz = t[CG_RZ] - 2.0 * a * t[CG_QZ] + a * a * t[CG_QQD];
         const double rr = t[CG_RR] - 2.0 * a * t[CG_QR] + a * a * t[CG_QQ];
@@ -1361,7 +1361,7 @@ __global__ void __launch_bounds__(TX * NTY) k_pcg_spmv_tiled(
             }
         }
     }
-    block_partials<CG_COLS, 0u>(acc, part_out);
+    block_partials<CG_COLS, 0u, true>(acc, part_out);
 }
 
 // Row form for n = 64 V H: a block of kRowWaves wavefronts owns kRowWaves / H
@@ -1390,11 +1390,6 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     static_assert(H == 1 ? kRowWaves >= 6 : H == 2 && kRowWaves == 8,
                   "y halo loads: wavefronts 0-5 (one per row) or 0-7 (two per row)");
     MEMBER(ph)
-    if (k > (st + mem_)->pcg.it_stop) return;   // see k_pcg_spmv
-    const CgHead h = cg_head(ph, (st + mem_)->pcg, MEMBER_FIRST(), mem_, k, part_in, nb_in, fresh,
-                             maxit);
-    const T alpha = (T)h.alpha, beta = (T)h.beta;
-    const T inv_h2 = (T)ph.inv_h2;
     const int n = ph.n, cz = ph.cz;   // n == 64 V
     constexpr int TY = kRowWaves / H, RW = 64 * H;   // rows per block, lanes per row
     const int lane = threadIdx.x, wv = threadIdx.y;
@@ -1403,8 +1398,11 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     const int k0 = bz_ * cz;
     const int k1 = k0 + cz < n ? k0 + cz : n;
     const size_t nn = (size_t)n * n;
-    __shared__ VT wl[TY + 4][RW];   // w of rows j0 - 2 .. j0 + TY + 1
-    __shared__ VT pl[TY + 2][RW];   // p of rows j0 - 1 .. j0 + TY
+    // rows of the current plane, two sets alternating with the plane's parity:
+    // a set is written again only two planes later, after every wavefront has
+    // passed the barrier of the plane in between (so one barrier per plane)
+    __shared__ VT wlb[2][TY + 4][RW];   // w of rows j0 - 2 .. j0 + TY + 1
+    __shared__ VT plb[2][TY + 2][RW];   // p of rows j0 - 1 .. j0 + TY
     auto wr = [n](int a) { return a < 0 ? a + n : (a >= n ? a - n : a); };
     auto ld = [](const T* f, size_t o) { return *reinterpret_cast<const VT*>(f + o); };
     // outputs and x stream past the caches (stream_st), keeping L2 for the
@@ -1412,21 +1410,6 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     auto st_v = [](T* f, size_t o, VT v) { stream_st(reinterpret_cast<VT*>(f + o), v); };
     auto ld_x = [](const T* f, size_t o) { return stream_ld(reinterpret_cast<const VT*>(f + o)); };
     const size_t col = base_ + (size_t)n * (j0 + r) + (size_t)V * gl;
-    const CgX<T> xu = cg_x<T, XM>((st + mem_)->pcg, k, h.alpha, xzero);
-    if (h.stop) {
-        if ((UPD || xzero) && !h.skip) {
-            for (int kk = k0; kk < k1; ++kk) {
-                const size_t Q = col + nn * (size_t)kk;
-                st_v(x, Q, XE    ? xu.two(ld(x, Q), ld(pold2, Q), ld(pold, Q))
-                           : UPD ? xu.one(ld(x, Q), ld(pold, Q))
-                                 : VT(T(0)));
-            }
-        }
-        return;
-    }
-    // r_k and p_k of a cell from its r_{k-1}, q_{k-1}, diag, p_{k-1}
-    auto resf = [&](VT ro, VT qo) -> VT { return UPD ? ro - alpha * qo : ro; };
-    auto dirf = [&](VT z, VT po) -> VT { return UPD ? z + beta * po : z; };
     auto ldu = [&](const T* f, size_t o) { return UPD ? ld(f, o) : VT(T(0)); };
     // this wavefront's y halo loads (h1..h4 from hsrc..hqsrc at hc1..hc4).
     // H = 1: w rows j0-2, j0-1, j0+TY, j0+TY+1 (waves 0-3), p rows j0-1,
@@ -1453,28 +1436,54 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     const T* hosrc = phalo ? pold : w;
     const T* hqsrc = phalo ? qold : w;
     auto plane = [&](int kk) { return nn * (size_t)wr(kk); };
+    // The first planes' loads go out before the launch's serial head (the
+    // stop test, the reduction of the previous iteration's partials, alpha
+    // and beta), which they do not depend on, so that their latency overlaps
+    // it; the head's barriers order LDS only and leave them in flight.
     const VT wmm = ld(w, col + plane(k0 - 2));
     VT wm1 = ld(w, col + plane(k0 - 1)), w0 = ld(w, col + plane(k0)), wp1 = ld(w, col + plane(k0 + 1));
     VT wp2n = ld(w, col + plane(k0 + 2));
     const size_t Qm = col + plane(k0 - 1), Q0 = col + plane(k0), Q1 = col + plane(k0 + 1);
-    auto jv = [](VT d) {
-        VT o;
-#pragma unroll
-        for (int i = 0; i < V; ++i) o[i] = jinv(d[i]);
-        return o;
-    };
-    VT pm = dirf(resf(ld(rin, Qm), ldu(qold, Qm)) * jv(ld(diag, Qm)), ldu(pold, Qm));
+    const VT rm_in = ld(rin, Qm), qm_in = ldu(qold, Qm), dm_in = ld(diag, Qm), om_in = ldu(pold, Qm);
     VT oc = ldu(pold, Q0);   // p_old of the current plane (x update)
     VT dc = ld(diag, Q0);
-    VT rc = resf(ld(rin, Q0), ldu(qold, Q0));
-    VT ic = jv(dc), zc = rc * ic;
-    VT pc = dirf(zc, oc);
+    const VT r0_in = ld(rin, Q0), q0_in = ldu(qold, Q0);
     // XE: x and p_{k-2} of the current plane and one plane ahead
     VT xc = XE ? ld_x(x, Q0) : VT(T(0)), xn1 = xc;
     VT o2c = XE ? ld_x(pold2, Q0) : VT(T(0)), o2n1 = o2c;
     VT rnx = ld(rin, Q1), qnx = ldu(qold, Q1), dnx = ld(diag, Q1), onx = ldu(pold, Q1);
     VT h1 = ld(hsrc, hc1 + plane(k0)), h2 = ld(hdsrc, hc2 + plane(k0));
     VT h3 = ldu(hosrc, hc3 + plane(k0)), h4 = ldu(hqsrc, hc4 + plane(k0));
+    if (k > (st + mem_)->pcg.it_stop) return;   // see k_pcg_spmv
+    const CgHead h = cg_head(ph, (st + mem_)->pcg, MEMBER_FIRST(), mem_, k, part_in, nb_in, fresh,
+                             maxit);
+    const T alpha = (T)h.alpha, beta = (T)h.beta;
+    const T inv_h2 = (T)ph.inv_h2;
+    const CgX<T> xu = cg_x<T, XM>((st + mem_)->pcg, k, h.alpha, xzero);
+    if (h.stop) {
+        if ((UPD || xzero) && !h.skip) {
+            for (int kk = k0; kk < k1; ++kk) {
+                const size_t Q = col + nn * (size_t)kk;
+                st_v(x, Q, XE    ? xu.two(ld(x, Q), ld(pold2, Q), ld(pold, Q))
+                           : UPD ? xu.one(ld(x, Q), ld(pold, Q))
+                                 : VT(T(0)));
+            }
+        }
+        return;
+    }
+    // r_k and p_k of a cell from its r_{k-1}, q_{k-1}, diag, p_{k-1}
+    auto resf = [&](VT ro, VT qo) -> VT { return UPD ? ro - alpha * qo : ro; };
+    auto dirf = [&](VT z, VT po) -> VT { return UPD ? z + beta * po : z; };
+    auto jv = [](VT d) {
+        VT o;
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = jinv(d[i]);
+        return o;
+    };
+    VT pm = dirf(resf(rm_in, qm_in) * jv(dm_in), om_in);
+    VT rc = resf(r0_in, q0_in);
+    VT ic = jv(dc), zc = rc * ic;
+    VT pc = dirf(zc, oc);
     VT kzm = (T(9) * (wm1 + w0) - (wmm + wp1)) * T(0.0625);
     auto from_left = [&](T v) { return __shfl(v, (lane + 63) & 63, 64); };
     auto from_right = [&](T v) { return __shfl(v, (lane + 1) & 63, 64); };
@@ -1508,6 +1517,8 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
                 o2n1 = ld_x(pold2, Qx);
             }
         }
+        VT(&wl)[TY + 4][RW] = wlb[kk & 1];
+        VT(&pl)[TY + 2][RW] = plb[kk & 1];
         wl[r + 2][gl] = w0;
         pl[r + 1][gl] = pc;
         if (H == 1) {
@@ -1534,7 +1545,6 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
             pL = pl[r + 1][gm];
             pR = pl[r + 1][gp];
         }
-        lds_barrier();
         // w at x - 2 .. x + V + 1 and p at x - 1 .. x + V of this lane's cells
         T wx[V + 4], px[V + 2];
         if (H == 1) {
@@ -1597,7 +1607,7 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
         ic = ip;
         dc = dn;
     }
-    block_partials<CG_COLS, 0u>(acc, part_out);
+    block_partials<CG_COLS, 0u, true>(acc, part_out);
 }
 
 // ---- CG preconditioned by a Chebyshev polynomial (stand-alone solve) ----

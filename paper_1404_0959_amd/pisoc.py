@@ -46,7 +46,7 @@ EXPORTED = [
     "pisoc_ens_get_stats", "pisoc_ens_time", "pisoc_ens_steps_done", "pisoc_ens_num_classes",
     "pisoc_ens_class_info", "pisoc_ens_autotune", "pisoc_ens_destroy", "pisoc_ens_last_error",
     "pisoc_diag_spectrum_bins", "pisoc_diag_workspace_bytes", "pisoc_diag_spectrum",
-    "pisoc_diag_qcrit", "pisoc_diag_sgs",
+    "pisoc_diag_qcrit", "pisoc_diag_sgs", "pisoc_stream_probe",
 ]
 ENS_EAGER, ENS_GRAPH, ENS_GRAPH_ONE = 0, 1, 2
 NET_NWEIGHTS = 15120
@@ -209,6 +209,8 @@ def lib():
     L.pisoc_diag_qcrit.restype = C.c_int
     L.pisoc_diag_sgs.argtypes = [i32, vp, C.POINTER(f64), vp, sz, vp]
     L.pisoc_diag_sgs.restype = C.c_int
+    L.pisoc_stream_probe.argtypes = [i32, i32, C.c_int64, C.POINTER(vp), C.POINTER(vp), i32, vp]
+    L.pisoc_stream_probe.restype = C.c_int
     _lib = L
     return L
 
@@ -701,3 +703,19 @@ def sgs_stats(u, stream=None):
     if st != OK:
         raise PisocError(st, "pisoc_diag_sgs")
     return tuple(out)
+
+
+def stream_probe(ins, outs, blocks=0, stream=None):
+    """One launch of the streaming probe: outs[w] = (w + 1) * sum(ins) over
+    FP32 device tensors of one size (the HBM ceiling of that read/write mix)."""
+    torch = _torch()
+    count = ins[0].numel()
+    if any(t.dtype != torch.float32 or t.numel() != count or not t.is_contiguous()
+           for t in list(ins) + list(outs)):
+        raise PisocError(ERR_INVALID, "stream_probe: contiguous FP32 tensors of one size")
+    pin = (C.c_void_p * len(ins))(*[t.data_ptr() for t in ins])
+    pout = (C.c_void_p * len(outs))(*[t.data_ptr() for t in outs])
+    st = lib().pisoc_stream_probe(len(ins), len(outs), count, pin, pout, blocks,
+                                  _stream_ptr(torch, stream))
+    if st != OK:
+        raise PisocError(st, "pisoc_stream_probe")

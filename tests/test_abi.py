@@ -182,6 +182,25 @@ def test_noalloc_solve_rejects_before_gpu_work(lib):
                                         None, None) == P.ERR_INVALID
 
 
+def test_stream_probe_rejects_before_gpu_work(lib):
+    """The streaming probe checks its counts and pointers before any GPU work."""
+    ins = (ctypes.c_void_p * 8)(*[256] * 8)
+    outs = (ctypes.c_void_p * 4)(*[4096] * 4)
+    for reads, writes, count, blocks in ((0, 1, 64, 0), (9, 1, 64, 0), (1, 0, 64, 0),
+                                         (1, 5, 64, 0), (1, 1, 62, 0), (1, 1, -4, 0),
+                                         (1, 1, 64, -1)):
+        assert lib.pisoc_stream_probe(reads, writes, count, ins, outs, blocks,
+                                      None) == P.ERR_INVALID
+    assert lib.pisoc_stream_probe(1, 1, 64, None, outs, 0, None) == P.ERR_INVALID
+    misaligned = (ctypes.c_void_p * 2)(256, 260)
+    assert lib.pisoc_stream_probe(2, 1, 64, misaligned, outs, 0, None) == P.ERR_INVALID
+    nulls = (ctypes.c_void_p * 2)(256, None)
+    assert lib.pisoc_stream_probe(1, 2, 64, ins, nulls, 0, None) == P.ERR_INVALID
+    # nothing to do: no launch, no device touched, the pointers not read
+    assert lib.pisoc_stream_probe(1, 1, 0, ins, outs, 0, None) == P.OK
+    assert lib.pisoc_stream_probe(1, 1, 0, None, None, 0, None) == P.OK
+
+
 # C structs of the header and their ctypes mirrors in the binding
 STRUCTS = {"pisoc_params": P.Params, "pisoc_step_info": P.StepInfo, "pisoc_stats": P.Stats,
            "pisoc_ens_class": P.EnsClass, "pisoc_kernel_stat": P.KernelStat}

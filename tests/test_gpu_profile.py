@@ -49,3 +49,25 @@ def test_profile_counts_cg_iterations(P):
     for name, rec in prof.items():
         assert rec["launches"] > 0 and rec["ms"] > 0.0, (name, rec)
     print({k: (v["launches"], round(1e3 * v["ms"] / v["launches"], 1)) for k, v in prof.items()})
+
+
+@pytest.mark.parametrize("reads,writes,blocks", [(1, 1, 0), (3, 2, 7), (5, 3, 0), (8, 4, 3)])
+def test_stream_probe_outputs(P, reads, writes, blocks):
+    """The streaming probe (the ceiling the memory-bound kernels are read
+    against) writes outs[w] = (w + 1) * (in_0 + ... + in_{R-1}), summed left
+    to right in FP32, bitwise, also over a grid of a few blocks that strides
+    many times; count 0 is a no-op."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(reads * 10 + writes)
+    count = 4 * 12345
+    ins = [torch.randn(count, device="cuda", generator=g) for _ in range(reads)]
+    outs = [torch.full((count,), float("nan"), device="cuda") for _ in range(writes)]
+    P.stream_probe(ins, outs, blocks=blocks)
+    torch.cuda.synchronize()
+    acc = torch.zeros(count, device="cuda")
+    for t in ins:
+        acc = acc + t
+    for w, o in enumerate(outs):
+        assert torch.equal(o, acc * float(w + 1)), w
+    empty = [torch.empty(0, device="cuda")]
+    P.stream_probe(empty, [torch.empty(0, device="cuda")])
