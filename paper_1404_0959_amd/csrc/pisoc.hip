@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -144,7 +145,10 @@ struct Prof {
                 }
             }
             float ms = 0.f;
-            if (working > 0 && hipEventElapsedTime(&ms, pool[r0.ea], pool[r0.eb]) == hipSuccess) {
+            // the GPU is past both events (see sync_state); the wait only
+            // lets the runtime see it
+            if (working > 0 && hipEventSynchronize(pool[r0.eb]) == hipSuccess &&
+                hipEventElapsedTime(&ms, pool[r0.ea], pool[r0.eb]) == hipSuccess) {
                 stat[r0.cls].launches += working;
                 stat[r0.cls].ms += ms;
                 stat[r0.cls].bytes += bytes;
@@ -293,6 +297,13 @@ struct pisoc_ctx {
     Launch TS;      // tiled launch of the CG kernel (nblocks = 0: none)
     DevState* st;
     DevState* hst = nullptr;  // pinned host copy (batch entries)
+    // publication of the state without a copy engine (see sync_state): hst is
+    // coherent host memory followed by a sequence number; hst_dev, seq_dev
+    // their device addresses (null: the plain copy and stream sync)
+    DevState* hst_dev = nullptr;
+    unsigned long long* seq_host = nullptr;
+    unsigned long long* seq_dev = nullptr;
+    unsigned long long seq = 0;
     double* partials;
     // rotating buffers
     int u_idx[3];   // which of lay.u3 holds u^n, work a, work b
@@ -374,8 +385,47 @@ void timed(pisoc_ctx* ctx, int cls, double words, int k, F&& launch) {
     P.pending.push_back({cls, a, b, words * (double)ctx->es * (double)ctx->NT(), k, 0.0});
 }
 
+// The device state published to the host: one wavefront copies the records
+// into the coherent pinned buffer, waits for its stores to complete at system
+// scope, then stores the sequence number v (release, system scope).  After
+// every earlier launch on the stream, so seeing v means those have finished.
+__global__ void __launch_bounds__(64) k_publish(const unsigned long long* __restrict__ src,
+                                                unsigned long long* dst, unsigned words,
+                                                unsigned long long* seq, unsigned long long v) {
+    for (unsigned i = threadIdx.x; i < words; i += 64) dst[i] = src[i];
+    __threadfence_system();
+    if (threadIdx.x == 0) __hip_atomic_store(seq, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Bring the device state to ctx->hst once the stream's work so far is done.
+// With the publication buffer the host spins on the sequence number (no copy
+// engine, no sleep in the runtime's wait: the GPU stays idle for less time
+// between the work before and the launches the host then makes); after
+// kPublishSpin without it, the stream sync decides (a long queue, or an
+// error on the stream).
+constexpr auto kPublishSpin = std::chrono::milliseconds(50);
+
 pisoc_status sync_state(pisoc_ctx* ctx) {
     HIP_TRY(ctx, hipGetLastError());
+    if (ctx->seq_host) {
+        const unsigned long long v = ++ctx->seq;
+        static_assert(sizeof(DevState) % 8 == 0, "DevState is copied in 8-byte words");
+        hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, ctx->stream,
+                           reinterpret_cast<const unsigned long long*>(ctx->st),
+                           reinterpret_cast<unsigned long long*>(ctx->hst_dev),
+                           (unsigned)(sizeof(DevState) / 8 * (size_t)ctx->batch), ctx->seq_dev, v);
+        HIP_TRY(ctx, hipGetLastError());
+        const auto t0 = std::chrono::steady_clock::now();
+        for (unsigned spin = 1;; ++spin) {
+            if (__atomic_load_n(ctx->seq_host, __ATOMIC_ACQUIRE) == v) return PISOC_OK;
+            if ((spin & 1023u) == 0 && std::chrono::steady_clock::now() - t0 > kPublishSpin) break;
+            __builtin_ia32_pause();
+        }
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        if (__atomic_load_n(ctx->seq_host, __ATOMIC_ACQUIRE) == v) return PISOC_OK;
+        ctx->err = "state publication not seen after the stream completed";
+        return PISOC_ERR_HIP;
+    }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->hst, ctx->st, sizeof(DevState) * (size_t)ctx->batch,
                                 hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -1029,7 +1079,8 @@ void audit_update(pisoc_ctx* ctx) {
         }
         A.it_guess[c] = mean(A.it_guess[c], it);
         float t_guess = 0.f, t_solve = 0.f;
-        if (hipEventElapsedTime(&t_guess, A.ev[c][0], A.ev[c][1]) == hipSuccess &&
+        if (hipEventSynchronize(A.ev[c][2]) == hipSuccess &&
+            hipEventElapsedTime(&t_guess, A.ev[c][0], A.ev[c][1]) == hipSuccess &&
             hipEventElapsedTime(&t_solve, A.ev[c][1], A.ev[c][2]) == hipSuccess && t_solve > 0.f)
             A.cost = mean(A.cost, (double)t_guess / ((double)t_solve / std::max(it, 1)));
     }
@@ -1316,11 +1367,27 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     }
     ctx->es = prm->precision == PISOC_FP64 ? sizeof(double) : sizeof(float);
     ctx->prof.reset();
-    if (hipHostMalloc(reinterpret_cast<void**>(&ctx->hst), sizeof(DevState) * (size_t)batch,
-                      hipHostMallocDefault) != hipSuccess) {
+    // the records, then the publication's sequence number (coherent memory:
+    // the GPU's stores reach the host while the stream still runs)
+    const size_t hbytes = sizeof(DevState) * (size_t)batch;
+    if (hipHostMalloc(reinterpret_cast<void**>(&ctx->hst), hbytes + 64,
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
         ctx->hst = nullptr;
         ctx->err = "hipHostMalloc failed";
         return PISOC_ERR_HIP;
+    }
+    {
+        void* dev = nullptr;
+        unsigned long long* seq = reinterpret_cast<unsigned long long*>(
+            reinterpret_cast<char*>(ctx->hst) + hbytes);
+        *seq = 0;
+        if (hipHostGetDevicePointer(&dev, ctx->hst, 0) == hipSuccess && dev) {
+            ctx->hst_dev = reinterpret_cast<DevState*>(dev);
+            ctx->seq_dev = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(dev) + hbytes);
+            ctx->seq_host = seq;
+        } else {
+            (void)hipGetLastError();   // the plain copy path then
+        }
     }
     hipStream_t s = ctx->stream;
     const size_t N = ctx->N();
@@ -1441,6 +1508,8 @@ void free_ctx(pisoc_ctx* ctx) {
     if (ctx->audit.have_events)
         for (auto& row : ctx->audit.ev)
             for (auto& e : row) (void)hipEventDestroy(e);
+    // no publication may still be on its way into the buffer
+    if (ctx->seq_host && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->hst) (void)hipHostFree(ctx->hst);
     delete ctx;
 }
