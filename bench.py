@@ -305,8 +305,10 @@ KERNEL_SOURCES = ("kernels.hip", "device.hpp", "launch.hpp", "net.hip")
 # dominant kernel class -> the 256^3 kernels whose HBM bytes the committed
 # counter summary holds (template instances of one kernel class are averaged
 # over their working launches)
-TRAFFIC_NAME = {("k_pcg_spmv", "f32+f64"): tuple(f"k_pcg_spmv_rows<float, 4, 1, {m}>" for m in range(3)),
-                ("k_pcg_spmv", "f64"): tuple(f"k_pcg_spmv_rows<double, 2, 2, {m}>" for m in range(3))}
+TRAFFIC_NAME = {("k_pcg_spmv", "f32+f64"): tuple(f"k_pcg_spmv_rows<float, 4, 1, {m}, true>"
+                                                  for m in range(3)),
+                ("k_pcg_spmv", "f64"): tuple(f"k_pcg_spmv_rows<double, 2, 2, {m}, false>"
+                                             for m in range(3))}
 
 
 def measured_traffic(kernel, dtype, n):

@@ -1377,8 +1377,9 @@ __global__ void __launch_bounds__(TX * NTY) k_pcg_spmv_tiled(
 // (one half row each) and the w halo by 4-7 (both halves of one row each).  z
 // neighbours come from per-lane register queues, the lower z face coefficient
 // carried over from the plane below.  Prefetches past the chunk's last needed
-// plane are clamped to planes already read.
-template <typename T, int V, int H, int XM>
+// plane are clamped to planes already read.  NT: r, q and p_old of the main
+// rows load non-temporally (see Launch::nt).
+template <typename T, int V, int H, int XM, bool NT>
 __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     Phys ph, DevState* st, int k, const T* __restrict__ rin, T* __restrict__ rout,
     const T* __restrict__ diag, const T* __restrict__ w, const T* __restrict__ pold,
@@ -1411,6 +1412,9 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
     auto ld_x = [](const T* f, size_t o) { return stream_ld(reinterpret_cast<const VT*>(f + o)); };
     const size_t col = base_ + (size_t)n * (j0 + r) + (size_t)V * gl;
     auto ldu = [&](const T* f, size_t o) { return UPD ? ld(f, o) : VT(T(0)); };
+    // the main rows' r, q, p_old of the planes ahead (read once per iteration)
+    auto ldm = [&](const T* f, size_t o) { return NT ? ld_x(f, o) : ld(f, o); };
+    auto ldmu = [&](const T* f, size_t o) { return UPD ? ldm(f, o) : VT(T(0)); };
     // this wavefront's y halo loads (h1..h4 from hsrc..hqsrc at hc1..hc4).
     // H = 1: w rows j0-2, j0-1, j0+TY, j0+TY+1 (waves 0-3), p rows j0-1,
     // j0+TY (waves 4-5, from r, q, diag and p_old); waves 6.. read their own
@@ -1503,10 +1507,10 @@ __global__ void __launch_bounds__(64 * kRowWaves) k_pcg_spmv_rows(
             const int kh = kk + 1 < k1 - 1 ? kk + 1 : k1 - 1;   // last halo plane: k1 - 1
             const size_t Qp = col + plane(kp), Qh = plane(kh);
             wp2n = ld(w, col + plane(kw));
-            rnx = ld(rin, Qp);
-            qnx = ldu(qold, Qp);
+            rnx = ldm(rin, Qp);
+            qnx = ldmu(qold, Qp);
             dnx = ld(diag, Qp);
-            onx = ldu(pold, Qp);
+            onx = ldmu(pold, Qp);
             h1 = ld(hsrc, hc1 + Qh);
             h2 = ld(hdsrc, hc2 + Qh);
             h3 = ldu(hosrc, hc3 + Qh);
@@ -3819,6 +3823,8 @@ Launch make_spmv_launch(int n, int batch, int elem_bytes, int cz_tile) {
         L.nz = nz;
         L.v = n / (64 * rh);
         L.h = rh;
+        const double field = (double)elem_bytes * n * n * n * batch;
+        L.nt = 9.0 * field > kMallBytes && 2.0 * field <= 0.6 * kMallBytes;
         return L;
     }
     const int TY = kTY * spmv_rows(elem_bytes);
@@ -4001,9 +4007,17 @@ static void spmv_launch(const Launch& L, const Launch& TL, hipStream_t s, const 
         Phys pt = ph;
         pt.cz = TL.cz;
         pt.nz = TL.nz;
-        if (TL.v == 2 && TL.h == 1) LAUNCH((k_pcg_spmv_rows<T, 2, 1, XM>), TL, s, pt, SPMV_ARGS);
-        else if (TL.v == 2) LAUNCH((k_pcg_spmv_rows<T, 2, 2, XM>), TL, s, pt, SPMV_ARGS);
-        else if constexpr (sizeof(T) == 4) LAUNCH((k_pcg_spmv_rows<T, 4, 1, XM>), TL, s, pt, SPMV_ARGS);
+        if (TL.nt) {
+            if (TL.v == 2 && TL.h == 1) LAUNCH((k_pcg_spmv_rows<T, 2, 1, XM, true>), TL, s, pt, SPMV_ARGS);
+            else if (TL.v == 2) LAUNCH((k_pcg_spmv_rows<T, 2, 2, XM, true>), TL, s, pt, SPMV_ARGS);
+            else if constexpr (sizeof(T) == 4)
+                LAUNCH((k_pcg_spmv_rows<T, 4, 1, XM, true>), TL, s, pt, SPMV_ARGS);
+        } else {
+            if (TL.v == 2 && TL.h == 1) LAUNCH((k_pcg_spmv_rows<T, 2, 1, XM, false>), TL, s, pt, SPMV_ARGS);
+            else if (TL.v == 2) LAUNCH((k_pcg_spmv_rows<T, 2, 2, XM, false>), TL, s, pt, SPMV_ARGS);
+            else if constexpr (sizeof(T) == 4)
+                LAUNCH((k_pcg_spmv_rows<T, 4, 1, XM, false>), TL, s, pt, SPMV_ARGS);
+        }
         return;
     }
     if (TL.nblocks) {
