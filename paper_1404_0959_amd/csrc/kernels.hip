@@ -658,7 +658,7 @@ __device__ inline void corr_rhs_store(size_t P, size_t N, double b, T dgT, const
     for (int d = 0; d < 3; ++d) stream_st(phiH + (d * N + P), phf[d]);
     const T bT = (T)b;
     stream_st(rvec + P, bT);
-    stream_st(diag + P, dgT);
+    diag[P] = dgT;   // read again by every CG iteration: through the caches
     const double bd = (double)bT;
     v[0] += bd * (bd / (double)dgT);
     v[1] += b64 ? b * b : bd * bd;
