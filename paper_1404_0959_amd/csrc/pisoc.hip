@@ -1370,13 +1370,18 @@ pisoc_status init_ctx(pisoc_ctx* ctx, const pisoc_params* mprm, int batch, char*
     // the records, then the publication's sequence number (coherent memory:
     // the GPU's stores reach the host while the stream still runs)
     const size_t hbytes = sizeof(DevState) * (size_t)batch;
-    if (hipHostMalloc(reinterpret_cast<void**>(&ctx->hst), hbytes + 64,
-                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
-        ctx->hst = nullptr;
-        ctx->err = "hipHostMalloc failed";
-        return PISOC_ERR_HIP;
+    bool coherent = hipHostMalloc(reinterpret_cast<void**>(&ctx->hst), hbytes + 64,
+                                  hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
+    if (!coherent) {   // the plain pinned copy and the stream sync then
+        (void)hipGetLastError();
+        if (hipHostMalloc(reinterpret_cast<void**>(&ctx->hst), hbytes + 64, hipHostMallocDefault) !=
+            hipSuccess) {
+            ctx->hst = nullptr;
+            ctx->err = "hipHostMalloc failed";
+            return PISOC_ERR_HIP;
+        }
     }
-    {
+    if (coherent) {
         void* dev = nullptr;
         unsigned long long* seq = reinterpret_cast<unsigned long long*>(
             reinterpret_cast<char*>(ctx->hst) + hbytes);
