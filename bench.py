@@ -338,18 +338,26 @@ def measured_traffic(kernel, dtype, n):
 
 
 STREAM_MIXES = ((1, 1), (3, 2), (5, 3), (7, 4))
+# FP32 words per cell each field kernel class reads and writes (the writes as
+# the WRITE_SIZE counter measures them, the reads the rest of the kernel's
+# algorithmic words); k_refine's mix depends on the round and is left out
+FIELD_MIXES = {"k_predict": (7, 4), "k_mom_source": (5, 3), "k_mom_sweep": (11, 3),
+               "k_hbya": (11, 5), "k_corr_rhs": (7, 7), "k_corr_update": (11, 7),
+               "k_dudt": (6, 3), "k_dust_flux": (9, 4), "k_dust_sweep": (6, 1),
+               "k_dust_finish": (5, 1)}
 
 
-def stream_ceiling(P, torch, n, reps=20):
-    """Practical HBM ceiling of the read/write mixes of the CG launches: the
-    library's plain streaming probe over n^3 FP32 fields, GB/s per mix (reads +
-    writes), timed with HIP events on the stream it runs on.  The CG moves
-    3 reads + 2 writes per cell at k = 0, 5 + 3 at odd k, 7 + 4 at even k."""
+def stream_ceiling(P, torch, n, mixes=STREAM_MIXES, reps=20):
+    """Practical HBM ceiling of read/write mixes: the library's plain streaming
+    probe over n^3 FP32 fields, GB/s per mix (reads + writes), timed with HIP
+    events on the stream it runs on.  The CG moves 3 reads + 2 writes per cell
+    at k = 0, 5 + 3 at odd k, 7 + 4 at even k."""
     count = n ** 3 // 4 * 4
-    bufs = [torch.ones(count, dtype=torch.float32, device="cuda") for _ in range(11)]
+    rmax, wmax = max(r for r, _ in mixes), max(w for _, w in mixes)
+    bufs = [torch.ones(count, dtype=torch.float32, device="cuda") for _ in range(rmax + wmax)]
     out = {}
-    for r, w in STREAM_MIXES:
-        ins, outs = bufs[:r], bufs[7:7 + w]
+    for r, w in mixes:
+        ins, outs = bufs[:r], bufs[rmax:rmax + w]
         for _ in range(3):
             P.stream_probe(ins, outs)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -433,7 +441,15 @@ def main():
     roof, kernels = roofline(H["prof"])
     roof["traffic"] = measured_traffic(roof["kernel"], "f64" if head == "fp64" else "f32+f64",
                                        args.n)
-    gbs = stream_ceiling(P, torch, args.n)
+    f32 = head != "fp64"
+    mixes = sorted(set(STREAM_MIXES) | (set(FIELD_MIXES.values()) if f32 else set()))
+    gbs = stream_ceiling(P, torch, args.n, mixes)
+    if f32:   # each FP32 field kernel against the stream of its own mix
+        for k, rec in kernels.items():
+            if k in FIELD_MIXES:
+                r, w = FIELD_MIXES[k]
+                rec["ceiling_gbs"] = gbs[f"{r}r{w}w"]
+                rec["of_ceiling"] = round(rec["gbs"] / gbs[f"{r}r{w}w"], 3)
     # odd and even CG iterations alternate: 8 and 11 words per cell, bytes-weighted
     mix = 19.0 / (8.0 / gbs["5r3w"] + 11.0 / gbs["7r4w"])
     roof["ceiling"] = {"kind": "streaming probe (k_stream), same read/write mixes, n^3 FP32 fields",

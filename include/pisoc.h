@@ -517,7 +517,7 @@ pisoc_status pisoc_diag_sgs(int32_t n, const double* d_u, double* h_out, void* d
  * with a grid stride and non-temporal loads and stores, in `blocks` blocks of
  * 256 threads (0: 16384).  h_in[reads], h_out[writes]: host arrays of device
  * pointers, each 16-byte aligned, count floats each; outputs must not
- * overlap inputs.  1 <= reads <= 8, 1 <= writes <= 4, count a multiple of 4.
+ * overlap inputs.  1 <= reads <= 12, 1 <= writes <= 8, count a multiple of 4.
  * count 0 does nothing (the pointers are not read).  Asynchronous on
  * hip_stream.  Errors: PISOC_ERR_INVALID (before any GPU work) for arguments
  * outside these ranges or a NULL or misaligned pointer; PISOC_ERR_HIP when

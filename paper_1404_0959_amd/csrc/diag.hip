@@ -19,9 +19,11 @@
 // ceiling of a given mix of reads and writes (no stencil, no reduction).
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <new>
+#include <utility>
 
 #include "../../include/pisoc.h"
 #include "device.hpp"
@@ -354,9 +356,10 @@ DiagLayout diag_layout(int n) {
 // non-temporal loads and stores (as the step's kernels stream their fields).
 constexpr int kStreamThreads = 256, kStreamBlocks = 16384;
 typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int kStreamMaxReads = 12, kStreamMaxWrites = 8;
 struct StreamPtrs {
-    const f4v* in[8];
-    f4v* out[4];
+    const f4v* in[kStreamMaxReads];
+    f4v* out[kStreamMaxWrites];
 };
 
 template <int R, int W>
@@ -371,15 +374,23 @@ __global__ void __launch_bounds__(kStreamThreads) k_stream(StreamPtrs p, size_t 
     }
 }
 
-template <int R>
-void launch_stream(int writes, dim3 g, hipStream_t s, const StreamPtrs& p, size_t n4) {
-    switch (writes) {
-    case 1: hipLaunchKernelGGL((k_stream<R, 1>), g, dim3(kStreamThreads), 0, s, p, n4); break;
-    case 2: hipLaunchKernelGGL((k_stream<R, 2>), g, dim3(kStreamThreads), 0, s, p, n4); break;
-    case 3: hipLaunchKernelGGL((k_stream<R, 3>), g, dim3(kStreamThreads), 0, s, p, n4); break;
-    default: hipLaunchKernelGGL((k_stream<R, 4>), g, dim3(kStreamThreads), 0, s, p, n4); break;
-    }
+template <int R, int W>
+void launch_stream_rw(dim3 g, hipStream_t s, const StreamPtrs& p, size_t n4) {
+    hipLaunchKernelGGL((k_stream<R, W>), g, dim3(kStreamThreads), 0, s, p, n4);
 }
+
+// launchers of k_stream<R, W>, R = 1..kStreamMaxReads, W = 1..kStreamMaxWrites
+using StreamLaunch = void (*)(dim3, hipStream_t, const StreamPtrs&, size_t);
+template <int R, int... Ws>
+constexpr std::array<StreamLaunch, sizeof...(Ws)> stream_row(std::integer_sequence<int, Ws...>) {
+    return {{&launch_stream_rw<R, Ws + 1>...}};
+}
+template <int... Rs>
+constexpr std::array<std::array<StreamLaunch, kStreamMaxWrites>, sizeof...(Rs)> stream_table(
+    std::integer_sequence<int, Rs...>) {
+    return {{stream_row<Rs + 1>(std::make_integer_sequence<int, kStreamMaxWrites>{})...}};
+}
+constexpr auto kStreamLaunch = stream_table(std::make_integer_sequence<int, kStreamMaxReads>{});
 
 }  // namespace
 }  // namespace pisoc
@@ -504,7 +515,8 @@ pisoc_status pisoc_diag_sgs(int32_t n, const double* d_u, double* h_out, void* d
 pisoc_status pisoc_stream_probe(int32_t reads, int32_t writes, int64_t count,
                                 const float* const* h_in, float* const* h_out, int32_t blocks,
                                 void* hip_stream) {
-    if (reads < 1 || reads > 8 || writes < 1 || writes > 4 || count < 0 || count % 4 != 0 ||
+    if (reads < 1 || reads > kStreamMaxReads || writes < 1 || writes > kStreamMaxWrites || count < 0 ||
+        count % 4 != 0 ||
         blocks < 0)
         return PISOC_ERR_INVALID;
     if (count == 0) return PISOC_OK;
@@ -521,16 +533,7 @@ pisoc_status pisoc_stream_probe(int32_t reads, int32_t writes, int64_t count,
     const size_t n4 = (size_t)count / 4;
     const dim3 g((unsigned)(blocks > 0 ? blocks : kStreamBlocks));
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    switch (reads) {
-    case 1: launch_stream<1>(writes, g, s, p, n4); break;
-    case 2: launch_stream<2>(writes, g, s, p, n4); break;
-    case 3: launch_stream<3>(writes, g, s, p, n4); break;
-    case 4: launch_stream<4>(writes, g, s, p, n4); break;
-    case 5: launch_stream<5>(writes, g, s, p, n4); break;
-    case 6: launch_stream<6>(writes, g, s, p, n4); break;
-    case 7: launch_stream<7>(writes, g, s, p, n4); break;
-    default: launch_stream<8>(writes, g, s, p, n4); break;
-    }
+    kStreamLaunch[reads - 1][writes - 1](g, s, p, n4);
     return hipGetLastError() == hipSuccess ? PISOC_OK : PISOC_ERR_HIP;
 }
 

@@ -184,10 +184,10 @@ def test_noalloc_solve_rejects_before_gpu_work(lib):
 
 def test_stream_probe_rejects_before_gpu_work(lib):
     """The streaming probe checks its counts and pointers before any GPU work."""
-    ins = (ctypes.c_void_p * 8)(*[256] * 8)
-    outs = (ctypes.c_void_p * 4)(*[4096] * 4)
-    for reads, writes, count, blocks in ((0, 1, 64, 0), (9, 1, 64, 0), (1, 0, 64, 0),
-                                         (1, 5, 64, 0), (1, 1, 62, 0), (1, 1, -4, 0),
+    ins = (ctypes.c_void_p * 12)(*[256] * 12)
+    outs = (ctypes.c_void_p * 8)(*[4096] * 8)
+    for reads, writes, count, blocks in ((0, 1, 64, 0), (13, 1, 64, 0), (1, 0, 64, 0),
+                                         (1, 9, 64, 0), (1, 1, 62, 0), (1, 1, -4, 0),
                                          (1, 1, 64, -1)):
         assert lib.pisoc_stream_probe(reads, writes, count, ins, outs, blocks,
                                       None) == P.ERR_INVALID

@@ -51,7 +51,8 @@ def test_profile_counts_cg_iterations(P):
     print({k: (v["launches"], round(1e3 * v["ms"] / v["launches"], 1)) for k, v in prof.items()})
 
 
-@pytest.mark.parametrize("reads,writes,blocks", [(1, 1, 0), (3, 2, 7), (5, 3, 0), (8, 4, 3)])
+@pytest.mark.parametrize("reads,writes,blocks", [(1, 1, 0), (3, 2, 7), (5, 3, 0), (8, 4, 3),
+                                                  (11, 7, 0), (12, 8, 5)])
 def test_stream_probe_outputs(P, reads, writes, blocks):
     """The streaming probe (the ceiling the memory-bound kernels are read
     against) writes outs[w] = (w + 1) * (in_0 + ... + in_{R-1}), summed left
