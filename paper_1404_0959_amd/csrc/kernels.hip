@@ -717,7 +717,7 @@ __global__ void __launch_bounds__(kBlock) k_corr_rhs(
 // kk + 4, resp. kk + 3) are issued after plane kk's work, a plane ahead of
 // their use, and clamped to the planes the chunk needs.  The per-cell
 // arithmetic is corr_rhs_cell, as in k_corr_rhs.  (FP32: at least four
-// wavefronts per SIMD, two blocks per CU, for 2 spilled values; 218 instead
+// wavefronts per SIMD, two blocks per CU, within 128 registers; 218 instead
 // of 238 us at 256^3.)
 template <typename T>
 __global__ void __launch_bounds__(kTX * kTY, sizeof(T) == 4 ? 4 : 2) k_corr_rhs_tiled(
